@@ -1,0 +1,293 @@
+"""CPU oracle for the Dressi hot path — TEST INFRASTRUCTURE ONLY.
+
+Only the test-suite, the smoke check and the benchmark's CPU-baseline leg may
+import this package.  It wraps ``liboracle.so`` (plain C, double precision,
+compiled from ``oracle.c`` with gcc) behind numpy-in / numpy-out functions.
+It shares no code with the GPU library.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB = os.path.join(HERE, "liboracle.so")
+SRC = os.path.join(HERE, "oracle.c")
+
+WRAP_REPEAT, WRAP_CLAMP = 0, 1
+TEX_2D, TEX_CUBE = 0, 1
+BLEND_HSR, BLEND_AA, BLEND_SOFTRAS, BLEND_HARD = 0, 1, 2, 3
+
+
+def build(openmp: bool = False) -> str:
+    """Compile liboracle.so with gcc (no contraction, no fast-math)."""
+    cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
+           "-shared", "-fPIC", "-o", LIB, SRC, "-lm"]
+    subprocess.check_call(cmd)
+    return LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+            build()
+        _lib = C.CDLL(LIB)
+    return _lib
+
+
+class _TexDesc(C.Structure):
+    _fields_ = [("kind", C.c_int), ("Ht", C.c_int), ("Wt", C.c_int), ("Ct", C.c_int),
+                ("wrap_u", C.c_int), ("wrap_v", C.c_int)]
+
+
+def _p(a):
+    return a.ctypes.data_as(C.c_void_p) if a is not None else None
+
+
+def _f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _u8(a):
+    return np.ascontiguousarray(a, dtype=np.uint8)
+
+
+def _check(rc, name):
+    if rc != 0:
+        raise RuntimeError(f"oracle {name} failed with status {rc}")
+
+
+# ---------------------------------------------------------------------------
+def rasterize(pos_clip, tris, H, W, K=1, r=0.0, cull=0):
+    """Returns tri_id [B,K,H,W] i32, hard [B,K,H,W] u8, bary [..,2] f64, dist f64."""
+    pc = _f32(pos_clip)
+    if pc.ndim == 2:
+        pc = pc[None]
+    B, V, _ = pc.shape
+    t = _i32(tris)
+    T = t.shape[0]
+    tri_id = np.empty((B, K, H, W), np.int32)
+    hard = np.empty((B, K, H, W), np.uint8)
+    bary = np.empty((B, K, H, W, 2), np.float64)
+    dist = np.empty((B, K, H, W), np.float64)
+    f = lib().orc_rasterize
+    f.argtypes = [C.c_void_p, C.c_void_p] + [C.c_int] * 6 + [C.c_float, C.c_int] + [C.c_void_p] * 4
+    _check(f(_p(pc), _p(t), B, V, T, H, W, K, C.c_float(r), cull,
+             _p(tri_id), _p(hard), _p(bary), _p(dist)), "rasterize")
+    return tri_id, hard, bary, dist
+
+
+def resolve(pos_clip, tris, tri_id, hard, snap=True, cull=0):
+    pc = _f32(pos_clip)
+    if pc.ndim == 2:
+        pc = pc[None]
+    B, V, _ = pc.shape
+    t = _i32(tris)
+    tid = _i32(tri_id)
+    _, K, H, W = tid.shape
+    bary = np.empty((B, K, H, W, 2), np.float64)
+    dist = np.empty((B, K, H, W), np.float64)
+    f = lib().orc_resolve
+    f.argtypes = [C.c_void_p, C.c_void_p] + [C.c_int] * 8 + [C.c_void_p] * 4
+    _check(f(_p(pc), _p(t), B, V, t.shape[0], H, W, K, cull, int(snap),
+             _p(tid), _p(_u8(hard)), _p(bary), _p(dist)), "resolve")
+    return bary, dist
+
+
+def rasterize_bwd(pos_clip, tris, tri_id, hard, grad_bary, grad_dist=None, snap=True, cull=0):
+    pc = _f32(pos_clip)
+    if pc.ndim == 2:
+        pc = pc[None]
+    B, V, _ = pc.shape
+    t = _i32(tris)
+    tid = _i32(tri_id)
+    _, K, H, W = tid.shape
+    gp = np.empty((B, V, 4), np.float64)
+    gd = _f64(grad_dist) if grad_dist is not None else None
+    f = lib().orc_rasterize_bwd
+    f.argtypes = [C.c_void_p, C.c_void_p] + [C.c_int] * 8 + [C.c_void_p] * 5
+    _check(f(_p(pc), _p(t), B, V, t.shape[0], H, W, K, cull, int(snap), _p(tid),
+             _p(_u8(hard)), _p(_f64(grad_bary)), _p(gd), _p(gp)), "rasterize_bwd")
+    return gp
+
+
+def interpolate(attr, attr_tris, tri_id, bary):
+    a = _f64(attr)
+    if a.ndim == 2:
+        a = a[None]
+    Ba, Va, Cc = a.shape
+    tid = _i32(tri_id)
+    B, K, H, W = tid.shape
+    at = _i32(attr_tris)
+    out = np.empty((B, K, H, W, Cc), np.float64)
+    f = lib().orc_interpolate
+    f.argtypes = [C.c_void_p] + [C.c_int] * 3 + [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p] \
+        + [C.c_int] * 4 + [C.c_void_p]
+    _check(f(_p(a), Ba, Va, Cc, _p(at), at.shape[0], _p(tid), _p(_f64(bary)), B, K, H, W,
+             _p(out)), "interpolate")
+    return out
+
+
+def interpolate_bwd(attr, attr_tris, tri_id, bary, grad_out):
+    a = _f64(attr)
+    squeeze = a.ndim == 2
+    if squeeze:
+        a = a[None]
+    Ba, Va, Cc = a.shape
+    tid = _i32(tri_id)
+    B, K, H, W = tid.shape
+    at = _i32(attr_tris)
+    ga = np.empty((Ba, Va, Cc), np.float64)
+    gb = np.empty((B, K, H, W, 2), np.float64)
+    f = lib().orc_interpolate_bwd
+    f.argtypes = [C.c_void_p] + [C.c_int] * 3 + [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p] \
+        + [C.c_int] * 4 + [C.c_void_p] * 3
+    _check(f(_p(a), Ba, Va, Cc, _p(at), at.shape[0], _p(tid), _p(_f64(bary)), B, K, H, W,
+             _p(_f64(grad_out)), _p(ga), _p(gb)), "interpolate_bwd")
+    return (ga[0] if squeeze else ga), gb
+
+
+def _desc(tex, kind, wrap_u, wrap_v):
+    if kind == TEX_CUBE:
+        F, Ht, Wt, Ct = tex.shape
+        assert F == 6
+    else:
+        Ht, Wt, Ct = tex.shape
+    return _TexDesc(kind, Ht, Wt, Ct, wrap_u, wrap_v)
+
+
+def texture(tex, coord, tri_id=None, kind=TEX_2D, wrap_u=WRAP_REPEAT, wrap_v=WRAP_CLAMP):
+    tx = _f64(tex)
+    d = _desc(tx, kind, wrap_u, wrap_v)
+    cd = 3 if kind == TEX_CUBE else 2
+    co = _f32(coord)
+    N = co.size // cd
+    out = np.empty(co.shape[:-1] + (d.Ct,), np.float64)
+    tid = _i32(tri_id) if tri_id is not None else None
+    f = lib().orc_texture
+    f.argtypes = [C.c_void_p, C.POINTER(_TexDesc), C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]
+    _check(f(_p(tx), C.byref(d), _p(co), _p(tid), N, _p(out)), "texture")
+    return out
+
+
+def texture_bwd_coord(tex, coord, grad_out, tri_id=None, kind=TEX_2D, wrap_u=WRAP_REPEAT,
+                      wrap_v=WRAP_CLAMP):
+    tx = _f64(tex)
+    d = _desc(tx, kind, wrap_u, wrap_v)
+    cd = 3 if kind == TEX_CUBE else 2
+    co = _f32(coord)
+    N = co.size // cd
+    g = np.empty(co.shape, np.float64)
+    tid = _i32(tri_id) if tri_id is not None else None
+    f = lib().orc_texture_bwd_coord
+    f.argtypes = [C.c_void_p, C.POINTER(_TexDesc), C.c_void_p, C.c_void_p, C.c_int64,
+                  C.c_void_p, C.c_void_p]
+    _check(f(_p(tx), C.byref(d), _p(co), _p(tid), N, _p(_f64(grad_out)), _p(g)), "texture_bwd_coord")
+    return g
+
+
+def invuv_build(tex_shape, coord, tri_id, kind=TEX_2D, wrap_u=WRAP_REPEAT, wrap_v=WRAP_CLAMP):
+    """coord [S,H,W,cd], tri_id [S,H,W] -> inv [S,(6,)Ht,Wt] i32."""
+    d = _desc(np.empty(tex_shape, np.float32), kind, wrap_u, wrap_v)
+    co = _f32(coord)
+    tid = _i32(tri_id)
+    S = tid.shape[0]
+    Npix = tid[0].size
+    F = 6 if kind == TEX_CUBE else 1
+    inv = np.empty((S, F, d.Ht, d.Wt), np.int32)
+    f = lib().orc_invuv_build
+    f.argtypes = [C.POINTER(_TexDesc), C.c_void_p, C.c_void_p, C.c_int, C.c_int64, C.c_void_p]
+    _check(f(C.byref(d), _p(co), _p(tid), S, Npix, _p(inv)), "invuv_build")
+    return inv if kind == TEX_CUBE else inv[:, 0]
+
+
+def texture_bwd_tex(tex_shape, coord, tri_id, grad_out, inv=None, kind=TEX_2D,
+                    wrap_u=WRAP_REPEAT, wrap_v=WRAP_CLAMP):
+    """Texture gradient through the inverse UV; coord [S,H,W,cd], grad_out [S,H,W,Ct]."""
+    d = _desc(np.empty(tex_shape, np.float32), kind, wrap_u, wrap_v)
+    co = _f32(coord)
+    tid = _i32(tri_id)
+    S = tid.shape[0]
+    Npix = tid[0].size
+    if inv is None:
+        inv = invuv_build(tex_shape, co, tid, kind, wrap_u, wrap_v)
+    gt = np.empty(tex_shape, np.float64)
+    f = lib().orc_texture_bwd_tex
+    f.argtypes = [C.POINTER(_TexDesc), C.c_void_p, C.c_void_p, C.c_int, C.c_int64, C.c_void_p,
+                  C.c_void_p, C.c_void_p]
+    _check(f(C.byref(d), _p(co), _p(tid), S, Npix, _p(_f64(grad_out)), _p(_i32(inv)), _p(gt)),
+           "texture_bwd_tex")
+    return gt
+
+
+def texture_adjoint(tex_shape, coord, tri_id, grad_out, kind=TEX_2D, wrap_u=WRAP_REPEAT,
+                    wrap_v=WRAP_CLAMP):
+    d = _desc(np.empty(tex_shape, np.float32), kind, wrap_u, wrap_v)
+    co = _f32(coord)
+    cd = 3 if kind == TEX_CUBE else 2
+    N = co.size // cd
+    gt = np.empty(tex_shape, np.float64)
+    tid = _i32(tri_id) if tri_id is not None else None
+    f = lib().orc_texture_adjoint
+    f.argtypes = [C.POINTER(_TexDesc), C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]
+    _check(f(C.byref(d), _p(co), _p(tid), N, _p(_f64(grad_out)), _p(gt)), "texture_adjoint")
+    return gt
+
+
+def edge_mask(tri_id, dist, delta, mode=BLEND_HSR):
+    tid = _i32(tri_id)
+    B, K, H, W = tid.shape
+    E = np.empty((B, H, W), np.uint8)
+    f = lib().orc_edge_mask
+    f.argtypes = [C.c_void_p, C.c_void_p] + [C.c_int] * 4 + [C.c_float, C.c_int, C.c_void_p]
+    dd = _f64(dist) if dist is not None else None
+    _check(f(_p(tid), _p(dd), B, K, H, W, C.c_float(delta), mode, _p(E)), "edge_mask")
+    return E
+
+
+def softras(color, dist, tri_id, sigma, delta, mode=BLEND_HSR):
+    tid = _i32(tri_id)
+    B, K, H, W = tid.shape
+    col = _f64(color)
+    Cc = col.shape[-1]
+    assert Cc <= 16
+    oc = np.empty((B, H, W, Cc), np.float64)
+    os_ = np.empty((B, H, W), np.float64)
+    E = np.empty((B, H, W), np.uint8)
+    dd = _f64(dist) if dist is not None else None
+    f = lib().orc_softras
+    f.argtypes = [C.c_void_p] * 3 + [C.c_int] * 5 + [C.c_double, C.c_float, C.c_int] + [C.c_void_p] * 3
+    _check(f(_p(col), _p(dd), _p(tid), B, K, H, W, Cc, sigma, C.c_float(delta), mode,
+             _p(oc), _p(os_), _p(E)), "softras")
+    return oc, os_, E
+
+
+def softras_bwd(color, dist, tri_id, sigma, E, grad_color, grad_sil):
+    tid = _i32(tri_id)
+    B, K, H, W = tid.shape
+    col = _f64(color)
+    Cc = col.shape[-1]
+    gl = np.empty((B, K, H, W, Cc), np.float64)
+    gd = np.empty((B, K, H, W), np.float64) if dist is not None else None
+    dd = _f64(dist) if dist is not None else None
+    gs = _f64(grad_sil) if grad_sil is not None else None
+    f = lib().orc_softras_bwd
+    f.argtypes = [C.c_void_p] * 3 + [C.c_int] * 5 + [C.c_double] + [C.c_void_p] * 5
+    _check(f(_p(col), _p(dd), _p(tid), B, K, H, W, Cc, sigma, _p(_u8(E)), _p(_f64(grad_color)),
+             _p(gs), _p(gl), _p(gd)), "softras_bwd")
+    return gl, gd

@@ -1,0 +1,1019 @@
+/*
+ * CPU oracle for the Dressi rasterization hot path (test infrastructure).
+ *
+ * This file is the plain, slow reference that the GPU library is checked
+ * against.  Only the tests, the smoke check and the CPU-baseline leg of the
+ * benchmark load it; the product path never does.  It shares no source, header
+ * or helper with the HIP library.
+ *
+ * Precision: every value is computed in double precision.  Where a floating
+ * point quantity decides an integer result (vertex snapping, the depth key, the
+ * soft-distance test and key, texel and cell selection, the edge-mask radius),
+ * the decision is taken in single precision with the operation order written
+ * out below, because the method's visibility is defined by those discrete
+ * choices and both implementations must take them identically.
+ *
+ * Paper references (Dressi, Eurographics 2022):
+ *   - rendering decomposition and loss: §3.4.1;
+ *   - HardSoftRas rasterization: Algorithm 2, §3.4.2 (Enlarge, SignedDist,
+ *     the Shift depth equation, depth peeling with K buffers);
+ *   - shading and blending: §3.4.3 (probability D_k = sigmoid(dist_k/sigma),
+ *     the edge/non-edge blend, colour and silhouette equations);
+ *   - inverse UV texture: §3.3.2, Algorithm 1;
+ *   - the listings of the appendix (BuildRasterize, BuildBlend, PeelDepth)
+ *     for the order of operations.
+ * Readings of passages the paper leaves open are stated where they are used.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include "oracle.h"
+
+#define SUBPIX 256 /* 8 sub-pixel bits */
+
+/* ------------------------------------------------------------------------ */
+/* Triangle setup                                                            */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int ok;           /* rasterizable */
+    int v[3];         /* vertex ids, reordered so that the area is positive */
+    int corner[3];    /* corner[i] = corner of tris[t] that vertex i came from */
+    int64_t X[3], Y[3]; /* snapped fixed-point screen coords (1/256 px)       */
+    int64_t A2;       /* twice the (positive) area in fixed point^2           */
+    float zn[3];      /* z/w in single precision (depth-key input)            */
+    double w[3];      /* clip w                                               */
+    double xn[3], yn[3]; /* x/w, y/w in double (used for the unsnapped mode)  */
+} otri;
+
+/* Viewport snap: x_px = (x/w + 1) * W/2 and y_px = (1 - y/w) * H/2 in float,
+ * then round-to-nearest-even of x_px * 256.  Rejects coordinates outside the
+ * +-2^22 guard band (also catches NaN). */
+static int snap_f32(float c, float w, float half, int is_y, int64_t *out)
+{
+    float n = c / w;
+    float p = is_y ? (1.0f - n) * half : (n + 1.0f) * half;
+    float f = p * 256.0f;
+    if (!(fabsf(f) < 4194304.0f)) return 0;
+    *out = (int64_t)nearbyintf(f);
+    return 1;
+}
+
+static otri setup_tri(const float *pc, const int32_t *tri, int H, int W, int cull)
+{
+    otri s;
+    memset(&s, 0, sizeof s);
+    float hw = 0.5f * (float)W, hh = 0.5f * (float)H;
+    int64_t X[3], Y[3];
+    float zn[3];
+    for (int i = 0; i < 3; i++) {
+        const float *p = pc + 4 * (int64_t)tri[i];
+        if (!(p[3] > 0.0f)) return s;            /* behind the eye: dropped */
+        if (!snap_f32(p[0], p[3], hw, 0, &X[i])) return s;
+        if (!snap_f32(p[1], p[3], hh, 1, &Y[i])) return s;
+        zn[i] = p[2] / p[3];
+    }
+    int64_t A2 = (X[1] - X[0]) * (Y[2] - Y[0]) - (X[2] - X[0]) * (Y[1] - Y[0]);
+    if (A2 == 0) return s;                       /* degenerate: dropped */
+    /* Screen y points down, so a positive A2 is clockwise in NDC (y up), i.e.
+     * a back face for counter-clockwise front faces. */
+    if (cull && A2 > 0) return s;
+    int order[3] = {0, 1, 2};
+    if (A2 < 0) { order[1] = 2; order[2] = 1; A2 = -A2; }
+    for (int i = 0; i < 3; i++) {
+        int c = order[i];
+        const float *p = pc + 4 * (int64_t)tri[c];
+        s.v[i] = tri[c];
+        s.corner[i] = c;
+        s.X[i] = X[c];
+        s.Y[i] = Y[c];
+        s.zn[i] = zn[c];
+        s.w[i] = (double)p[3];
+        s.xn[i] = (double)p[0] / (double)p[3];
+        s.yn[i] = (double)p[1] / (double)p[3];
+    }
+    s.A2 = A2;
+    s.ok = 1;
+    return s;
+}
+
+/* Edge function of the edge opposite vertex i (from vertex i+1 to i+2),
+ * evaluated at fixed-point point (px, py).  E_i(v_i) = A2 > 0. */
+static int64_t edge_fn(const otri *s, int i, int64_t px, int64_t py)
+{
+    int a = (i + 1) % 3, b = (i + 2) % 3;
+    return (s->X[b] - s->X[a]) * (py - s->Y[a]) - (s->Y[b] - s->Y[a]) * (px - s->X[a]);
+}
+
+/* Fill convention (the paper relies on the hardware's): a sample exactly on an
+ * edge belongs to the triangle that contains the sample nudged by an
+ * infinitesimal (eps, eps^2) to the right and down.  For E = dx*(py-ya) -
+ * dy*(px-xa) this owns E == 0 iff dy < 0, or dy == 0 and dx > 0 (the usual
+ * top-left rule).  Every point is thus covered exactly once by a tiling. */
+static int edge_owns_zero(const otri *s, int i)
+{
+    int a = (i + 1) % 3, b = (i + 2) % 3;
+    int64_t dx = s->X[b] - s->X[a], dy = s->Y[b] - s->Y[a];
+    return dy < 0 || (dy == 0 && dx > 0);
+}
+
+static int covers(const otri *s, int64_t px, int64_t py, int64_t E[3])
+{
+    int in = 1;
+    for (int i = 0; i < 3; i++) {
+        E[i] = edge_fn(s, i, px, py);
+        if (!(E[i] > 0 || (E[i] == 0 && edge_owns_zero(s, i)))) in = 0;
+    }
+    return in;
+}
+
+/* Depth key input: z = z0 + l1*(z1-z0) + l2*(z2-z0) with l_i = E_i/A2, all in
+ * float (int64 -> float rounds to nearest), summed left to right. */
+static float depth_f32(const otri *s, const int64_t E[3])
+{
+    float A = (float)s->A2;
+    float l1 = (float)E[1] / A;
+    float l2 = (float)E[2] / A;
+    float d1 = s->zn[1] - s->zn[0];
+    float d2 = s->zn[2] - s->zn[0];
+    float t1 = l1 * d1;
+    float t2 = l2 * d2;
+    float z = s->zn[0] + t1;
+    return z + t2;
+}
+
+/* Distance (fixed-point units) from (px,py) to the closed segment of edge i,
+ * evaluated in float from exact integer dot products. */
+static float seg_dist_f32(const otri *s, int i, int64_t px, int64_t py, int64_t E)
+{
+    int a = (i + 1) % 3, b = (i + 2) % 3;
+    int64_t ex = s->X[b] - s->X[a], ey = s->Y[b] - s->Y[a];
+    int64_t qx = px - s->X[a], qy = py - s->Y[a];
+    int64_t dot = qx * ex + qy * ey;
+    int64_t len2 = ex * ex + ey * ey;
+    if (dot <= 0) return sqrtf((float)(qx * qx + qy * qy));
+    if (dot >= len2) {
+        int64_t rx = px - s->X[b], ry = py - s->Y[b];
+        return sqrtf((float)(rx * rx + ry * ry));
+    }
+    int64_t ae = E < 0 ? -E : E;
+    return (float)ae / sqrtf((float)len2);
+}
+
+/* SignedDist magnitude decision (§3.4.2): the pixel's distance to the triangle
+ * boundary, i.e. the minimum over the three edge segments, in [0,1] screen
+ * units (pixels / W).  Returns the nearest edge (lowest index on ties). */
+static float dist_norm_f32(const otri *s, int64_t px, int64_t py, const int64_t E[3],
+                           int W, int *nearest)
+{
+    float best = 0.0f;
+    int bi = 0;
+    for (int i = 0; i < 3; i++) {
+        float d = seg_dist_f32(s, i, px, py, E[i]);
+        if (i == 0 || d < best) { best = d; bi = i; }
+    }
+    if (nearest) *nearest = bi;
+    return best / ((float)W * 256.0f);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Rasterization with K layers (Algorithm 2, Shift, PeelDepth)              */
+/* ------------------------------------------------------------------------ */
+
+typedef struct { float key; int32_t id; } frag;
+
+/* Layer k of a pixel is the k-th smallest *distinct* key among all of the
+ * pixel's fragments, carried by the smallest triangle id at that key.  This is
+ * what K passes of depth peeling give: PeelDepth discards keys <= the previous
+ * layer's key, and a LESS depth test keeps the first (lowest-id) primitive
+ * among equal keys.  The running list below is insertion into a sorted list of
+ * at most K distinct keys, which yields the same set in any visiting order. */
+static void klist_insert(frag *L, int *n, int K, float key, int32_t id)
+{
+    for (int j = 0; j < *n; j++) {
+        if (L[j].key == key) { if (id < L[j].id) L[j].id = id; return; }
+    }
+    int pos = *n;
+    while (pos > 0 && key < L[pos - 1].key) pos--;
+    if (pos >= K) return;
+    int last = (*n < K) ? *n : K - 1;
+    for (int j = last; j > pos; j--) L[j] = L[j - 1];
+    L[pos].key = key;
+    L[pos].id = id;
+    if (*n < K) (*n)++;
+}
+
+static void resolve_one(const otri *s, int px_i, int py_i, int hard, int snap,
+                        int H, int W, double *b0, double *b1, double *dist);
+
+int orc_rasterize(const float *pos_clip, const int32_t *tris, int B, int V, int T,
+                  int H, int W, int K, float r, int cull,
+                  int32_t *tri_id, uint8_t *hard, double *bary, double *dist)
+{
+    if (B < 0 || V < 0 || T < 0 || H <= 0 || W <= 0 || K < 1 || K > 5) return -1;
+    if (!(r >= 0.0f && r <= 1.0f)) return -1;
+    int64_t N = (int64_t)H * W;
+    frag *lists = (frag *)malloc(sizeof(frag) * (size_t)(N * K));
+    int *cnt = (int *)malloc(sizeof(int) * (size_t)N);
+    if (!lists || !cnt) { free(lists); free(cnt); return -2; }
+    /* pixels within r of a triangle lie at most ceil(r*W) + 2 pixels from its bbox */
+    int margin = (r > 0.0f) ? (int)ceil((double)r * W) + 2 : 0;
+    for (int b = 0; b < B; b++) {
+        const float *pc = pos_clip + (int64_t)b * V * 4;
+        memset(cnt, 0, sizeof(int) * (size_t)N);
+        for (int t = 0; t < T; t++) {
+            otri s = setup_tri(pc, tris + 3 * (int64_t)t, H, W, cull);
+            if (!s.ok) continue;
+            int64_t xmin = s.X[0], xmax = s.X[0], ymin = s.Y[0], ymax = s.Y[0];
+            for (int i = 1; i < 3; i++) {
+                if (s.X[i] < xmin) xmin = s.X[i];
+                if (s.X[i] > xmax) xmax = s.X[i];
+                if (s.Y[i] < ymin) ymin = s.Y[i];
+                if (s.Y[i] > ymax) ymax = s.Y[i];
+            }
+            int64_t x0 = (int64_t)floor(xmin / 256.0) - 1 - margin;
+            int64_t x1 = (int64_t)ceil(xmax / 256.0) + 1 + margin;
+            int64_t y0 = (int64_t)floor(ymin / 256.0) - 1 - margin;
+            int64_t y1 = (int64_t)ceil(ymax / 256.0) + 1 + margin;
+            if (x0 < 0) x0 = 0;
+            if (y0 < 0) y0 = 0;
+            if (x1 > W - 1) x1 = W - 1;
+            if (y1 > H - 1) y1 = H - 1;
+            for (int64_t y = y0; y <= y1; y++) {
+                for (int64_t x = x0; x <= x1; x++) {
+                    int64_t px = SUBPIX * x + SUBPIX / 2, py = SUBPIX * y + SUBPIX / 2;
+                    int64_t E[3];
+                    float key;
+                    if (covers(&s, px, py, E)) {
+                        /* hard fragment: Shift gives 0.5 * depth */
+                        float z = depth_f32(&s, E);
+                        if (!(z > 0.0f && z < 1.0f)) continue;
+                        key = 0.5f * z;
+                    } else {
+                        if (!(r > 0.0f)) continue;
+                        /* soft fragment: Shift gives 0.5 * |dist| + 0.5 */
+                        float dn = dist_norm_f32(&s, px, py, E, W, NULL);
+                        if (!(dn <= r)) continue;
+                        float h = 0.5f * dn;
+                        key = h + 0.5f;
+                    }
+                    int64_t p = y * W + x;
+                    klist_insert(lists + p * K, &cnt[p], K, key, t);
+                }
+            }
+        }
+        for (int64_t p = 0; p < N; p++) {
+            int y = (int)(p / W), x = (int)(p % W);
+            for (int k = 0; k < K; k++) {
+                int64_t o = (((int64_t)b * K + k) * H + y) * W + x;
+                if (k < cnt[p]) {
+                    int32_t t = lists[p * K + k].id;
+                    tri_id[o] = t;
+                    /* hard keys are < 0.5, soft keys >= 0.5 */
+                    int hd = lists[p * K + k].key < 0.5f;
+                    if (hard) hard[o] = (uint8_t)hd;
+                    otri s = setup_tri(pc, tris + 3 * (int64_t)t, H, W, cull);
+                    double b0, b1, d;
+                    resolve_one(&s, x, y, hd, 1, H, W, &b0, &b1, &d);
+                    if (bary) { bary[2 * o] = b0; bary[2 * o + 1] = b1; }
+                    if (dist) dist[o] = d;
+                } else {
+                    tri_id[o] = -1;
+                    if (hard) hard[o] = 0;
+                    if (bary) { bary[2 * o] = 0.0; bary[2 * o + 1] = 0.0; }
+                    if (dist) dist[o] = 0.0;
+                }
+            }
+        }
+    }
+    free(lists);
+    free(cnt);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Resolve: barycentrics and signed distance for a frozen fragment          */
+/* ------------------------------------------------------------------------ */
+
+/* Screen-space vertex positions in pixels: the snapped ones (X/256) when
+ * snap != 0, otherwise the exact ones computed in double (used for finite
+ * differences, where snapping would make the values piecewise constant). */
+static void screen_xy(const otri *s, int snap, int H, int W, double sx[3], double sy[3])
+{
+    for (int i = 0; i < 3; i++) {
+        if (snap) {
+            sx[i] = (double)s->X[i] / SUBPIX;
+            sy[i] = (double)s->Y[i] / SUBPIX;
+        } else {
+            sx[i] = (s->xn[i] + 1.0) * 0.5 * W;
+            sy[i] = (1.0 - s->yn[i]) * 0.5 * H;
+        }
+    }
+}
+
+/* Screen-linear barycentrics lambda_i = E_i / A2 (double), E_i for the edge
+ * opposite vertex i.  Soft fragments extrapolate (no clamping). */
+static void lambdas(const double sx[3], const double sy[3], double px, double py, double l[3])
+{
+    double A = (sx[1] - sx[0]) * (sy[2] - sy[0]) - (sx[2] - sx[0]) * (sy[1] - sy[0]);
+    for (int i = 0; i < 3; i++) {
+        int a = (i + 1) % 3, b = (i + 2) % 3;
+        double E = (sx[b] - sx[a]) * (py - sy[a]) - (sy[b] - sy[a]) * (px - sx[a]);
+        l[i] = E / A;
+    }
+}
+
+/* Closest point parameter on the segment of edge i and the distance to it. */
+static double seg_dist_d(const double sx[3], const double sy[3], int i, double px, double py,
+                         double *t_out)
+{
+    int a = (i + 1) % 3, b = (i + 2) % 3;
+    double ex = sx[b] - sx[a], ey = sy[b] - sy[a];
+    double t = ((px - sx[a]) * ex + (py - sy[a]) * ey) / (ex * ex + ey * ey);
+    if (t < 0.0) t = 0.0;
+    if (t > 1.0) t = 1.0;
+    double cx = sx[a] + t * ex, cy = sy[a] + t * ey;
+    if (t_out) *t_out = t;
+    return hypot(px - cx, py - cy);
+}
+
+/* Nearest edge: in snapped mode the single-precision decision of the
+ * rasterizer; otherwise the double-precision minimum. */
+static int nearest_edge(const otri *s, int snap, const double sx[3], const double sy[3],
+                        int x, int y, int W)
+{
+    if (snap) {
+        int64_t px = SUBPIX * (int64_t)x + SUBPIX / 2, py = SUBPIX * (int64_t)y + SUBPIX / 2;
+        int64_t E[3];
+        for (int i = 0; i < 3; i++) E[i] = edge_fn(s, i, px, py);
+        int ne;
+        dist_norm_f32(s, px, py, E, W, &ne);
+        return ne;
+    }
+    double best = 0.0;
+    int bi = 0;
+    for (int i = 0; i < 3; i++) {
+        double d = seg_dist_d(sx, sy, i, x + 0.5, y + 0.5, NULL);
+        if (i == 0 || d < best) { best = d; bi = i; }
+    }
+    return bi;
+}
+
+static void resolve_one(const otri *s, int x, int y, int hard, int snap,
+                        int H, int W, double *b0, double *b1, double *dist)
+{
+    double sx[3], sy[3], l[3], q[3], bn[3], bo[3];
+    screen_xy(s, snap, H, W, sx, sy);
+    double px = x + 0.5, py = y + 0.5;
+    lambdas(sx, sy, px, py, l);
+    /* perspective-correct barycentrics: b_i = (l_i/w_i) / sum_j (l_j/w_j) */
+    double Q = 0.0;
+    for (int i = 0; i < 3; i++) { q[i] = l[i] / s->w[i]; Q += q[i]; }
+    for (int i = 0; i < 3; i++) bn[i] = q[i] / Q;
+    for (int i = 0; i < 3; i++) bo[s->corner[i]] = bn[i];
+    *b0 = bo[0];
+    *b1 = bo[1];
+    int ne = nearest_edge(s, snap, sx, sy, x, y, W);
+    double d = seg_dist_d(sx, sy, ne, px, py, NULL) / W;
+    /* sign: + for hard (inside) fragments, - for soft ones; the sign bit
+     * carries the flag even at distance 0 */
+    *dist = hard ? d : -d;
+}
+
+int orc_resolve(const float *pos_clip, const int32_t *tris, int B, int V, int T,
+                int H, int W, int K, int cull, int snap,
+                const int32_t *tri_id, const uint8_t *hard, double *bary, double *dist)
+{
+    for (int b = 0; b < B; b++) {
+        const float *pc = pos_clip + (int64_t)b * V * 4;
+        for (int k = 0; k < K; k++)
+            for (int y = 0; y < H; y++)
+                for (int x = 0; x < W; x++) {
+                    int64_t o = (((int64_t)b * K + k) * H + y) * W + x;
+                    int32_t t = tri_id[o];
+                    if (t < 0 || t >= T) {
+                        if (bary) { bary[2 * o] = 0.0; bary[2 * o + 1] = 0.0; }
+                        if (dist) dist[o] = 0.0;
+                        continue;
+                    }
+                    otri s = setup_tri(pc, tris + 3 * (int64_t)t, H, W, cull);
+                    if (!s.ok) return -3;
+                    double b0, b1, d;
+                    resolve_one(&s, x, y, hard[o], snap, H, W, &b0, &b1, &d);
+                    if (bary) { bary[2 * o] = b0; bary[2 * o + 1] = b1; }
+                    if (dist) dist[o] = d;
+                }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Rasterization backward: d(bary, dist)/d(pos_clip) with frozen visibility */
+/* ------------------------------------------------------------------------ */
+
+/* Rasterize and PeelDepth have no backward in the paper; gradients reach the
+ * vertices only through the barycentrics and the signed distance, which are
+ * differentiable functions of the projected vertices.  Snapping is treated as
+ * the identity (straight-through), with values taken at the snapped point. */
+int orc_rasterize_bwd(const float *pos_clip, const int32_t *tris, int B, int V, int T,
+                      int H, int W, int K, int cull, int snap,
+                      const int32_t *tri_id, const uint8_t *hard,
+                      const double *grad_bary, const double *grad_dist, double *grad_pos)
+{
+    memset(grad_pos, 0, sizeof(double) * (size_t)B * V * 4);
+    for (int b = 0; b < B; b++) {
+        const float *pc = pos_clip + (int64_t)b * V * 4;
+        double *gp = grad_pos + (int64_t)b * V * 4;
+        for (int k = 0; k < K; k++)
+            for (int y = 0; y < H; y++)
+                for (int x = 0; x < W; x++) {
+                    int64_t o = (((int64_t)b * K + k) * H + y) * W + x;
+                    int32_t t = tri_id[o];
+                    if (t < 0 || t >= T) continue;
+                    otri s = setup_tri(pc, tris + 3 * (int64_t)t, H, W, cull);
+                    if (!s.ok) return -3;
+                    double sx[3], sy[3], l[3], q[3], bn[3];
+                    screen_xy(&s, snap, H, W, sx, sy);
+                    double px = x + 0.5, py = y + 0.5;
+                    lambdas(sx, sy, px, py, l);
+                    double Q = 0.0;
+                    for (int i = 0; i < 3; i++) { q[i] = l[i] / s.w[i]; Q += q[i]; }
+                    for (int i = 0; i < 3; i++) bn[i] = q[i] / Q;
+                    /* gradient w.r.t. the normalized-order barycentrics; b2 of
+                     * the original order is 1 - b0 - b1 and carries none */
+                    double go[3] = {grad_bary[2 * o], grad_bary[2 * o + 1], 0.0};
+                    double gb[3], gsx[3] = {0, 0, 0}, gsy[3] = {0, 0, 0}, gw[3];
+                    for (int i = 0; i < 3; i++) gb[i] = go[s.corner[i]];
+                    double sb = gb[0] * bn[0] + gb[1] * bn[1] + gb[2] * bn[2];
+                    double gl[3];
+                    for (int i = 0; i < 3; i++) {
+                        double gq = (gb[i] - sb) / Q;
+                        gl[i] = gq / s.w[i];
+                        gw[i] = -gq * l[i] / (s.w[i] * s.w[i]);
+                    }
+                    /* d lambda_i / d v_j = -lambda_j * grad_p lambda_i */
+                    double A = (sx[1] - sx[0]) * (sy[2] - sy[0]) - (sx[2] - sx[0]) * (sy[1] - sy[0]);
+                    double Gx = 0.0, Gy = 0.0;
+                    for (int i = 0; i < 3; i++) {
+                        int a = (i + 1) % 3, c = (i + 2) % 3;
+                        Gx += gl[i] * (-(sy[c] - sy[a]) / A);
+                        Gy += gl[i] * ((sx[c] - sx[a]) / A);
+                    }
+                    for (int j = 0; j < 3; j++) { gsx[j] -= l[j] * Gx; gsy[j] -= l[j] * Gy; }
+                    /* signed distance: d(dist)/d(endpoints) of the nearest segment */
+                    if (grad_dist) {
+                        double g = grad_dist[o];
+                        int ne = nearest_edge(&s, snap, sx, sy, x, y, W);
+                        double tt;
+                        double d = seg_dist_d(sx, sy, ne, px, py, &tt);
+                        if (d > 0.0 && g != 0.0) {
+                            int a = (ne + 1) % 3, c = (ne + 2) % 3;
+                            double cx = sx[a] + tt * (sx[c] - sx[a]);
+                            double cy = sy[a] + tt * (sy[c] - sy[a]);
+                            double ux = (px - cx) / d, uy = (py - cy) / d;
+                            double sg = (hard[o] ? 1.0 : -1.0) * g / W;
+                            gsx[a] += sg * (-(1.0 - tt) * ux);
+                            gsy[a] += sg * (-(1.0 - tt) * uy);
+                            gsx[c] += sg * (-tt * ux);
+                            gsy[c] += sg * (-tt * uy);
+                        }
+                    }
+                    /* screen -> clip: x_s = (x/w + 1) W/2, y_s = (1 - y/w) H/2 */
+                    for (int j = 0; j < 3; j++) {
+                        double w = s.w[j];
+                        double *g = gp + 4 * (int64_t)s.v[j];
+                        g[0] += gsx[j] * (0.5 * W) / w;
+                        g[1] += gsy[j] * (-0.5 * H) / w;
+                        g[3] += gsx[j] * (-0.5 * W) * s.xn[j] / w
+                              + gsy[j] * (0.5 * H) * s.yn[j] / w + gw[j];
+                    }
+                }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Attribute interpolation (BuildInterpolate)                                */
+/* ------------------------------------------------------------------------ */
+
+int orc_interpolate(const double *attr, int Ba, int Va, int C, const int32_t *attr_tris, int T,
+                    const int32_t *tri_id, const double *bary, int B, int K, int H, int W,
+                    double *out)
+{
+    int64_t N = (int64_t)K * H * W;
+    for (int b = 0; b < B; b++) {
+        const double *a = attr + (Ba == 1 ? 0 : (int64_t)b * Va * C);
+        for (int64_t p = 0; p < N; p++) {
+            int64_t o = (int64_t)b * N + p;
+            int32_t t = tri_id[o];
+            double *y = out + o * C;
+            if (t < 0 || t >= T) { for (int c = 0; c < C; c++) y[c] = 0.0; continue; }
+            double w0 = bary[2 * o], w1 = bary[2 * o + 1], w2 = 1.0 - w0 - w1;
+            const int32_t *tv = attr_tris + 3 * (int64_t)t;
+            for (int c = 0; c < C; c++)
+                y[c] = w0 * a[(int64_t)tv[0] * C + c] + w1 * a[(int64_t)tv[1] * C + c]
+                     + w2 * a[(int64_t)tv[2] * C + c];
+        }
+    }
+    return 0;
+}
+
+int orc_interpolate_bwd(const double *attr, int Ba, int Va, int C, const int32_t *attr_tris,
+                        int T, const int32_t *tri_id, const double *bary, int B, int K, int H,
+                        int W, const double *grad_out, double *grad_attr, double *grad_bary)
+{
+    int64_t N = (int64_t)K * H * W;
+    memset(grad_attr, 0, sizeof(double) * (size_t)Ba * Va * C);
+    for (int b = 0; b < B; b++) {
+        const double *a = attr + (Ba == 1 ? 0 : (int64_t)b * Va * C);
+        double *ga = grad_attr + (Ba == 1 ? 0 : (int64_t)b * Va * C);
+        for (int64_t p = 0; p < N; p++) {
+            int64_t o = (int64_t)b * N + p;
+            int32_t t = tri_id[o];
+            if (t < 0 || t >= T) { grad_bary[2 * o] = 0.0; grad_bary[2 * o + 1] = 0.0; continue; }
+            double w[3] = {bary[2 * o], bary[2 * o + 1], 0.0};
+            w[2] = 1.0 - w[0] - w[1];
+            const int32_t *tv = attr_tris + 3 * (int64_t)t;
+            const double *g = grad_out + o * C;
+            double g0 = 0.0, g1 = 0.0;
+            for (int c = 0; c < C; c++) {
+                double a0 = a[(int64_t)tv[0] * C + c], a1 = a[(int64_t)tv[1] * C + c];
+                double a2 = a[(int64_t)tv[2] * C + c];
+                g0 += g[c] * (a0 - a2);
+                g1 += g[c] * (a1 - a2);
+                for (int i = 0; i < 3; i++) ga[(int64_t)tv[i] * C + c] += w[i] * g[c];
+            }
+            grad_bary[2 * o] = g0;
+            grad_bary[2 * o + 1] = g1;
+        }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Bilinear texture sampling (the sampler behind GLSL texture())             */
+/* ------------------------------------------------------------------------ */
+
+/* Taps along one axis: s = u*n - 1/2 in float, i0 = floor(s), f = s - i0.
+ * Wrap: repeat (mod n) or clamp (index clamped).  Returns the wrapped taps. */
+static void taps_1d(float u, int n, int wrap, int *i0, int *i1, double *f)
+{
+    float s = u * (float)n;
+    s = s - 0.5f;
+    float fl = floorf(s);
+    float fr = s - fl;
+    int a = (int)fl, b = a + 1;
+    if (wrap == ORC_WRAP_REPEAT) {
+        a %= n; if (a < 0) a += n;
+        b %= n; if (b < 0) b += n;
+    } else {
+        if (a < 0) a = 0;
+        if (a > n - 1) a = n - 1;
+        if (b < 0) b = 0;
+        if (b > n - 1) b = n - 1;
+    }
+    *i0 = a;
+    *i1 = b;
+    *f = (double)fr;
+}
+
+/* The cell of Algorithm 1 ("normalize UV, store at p_tex"): floor(u * n),
+ * wrapped or clamped like the taps. */
+static int cell_1d(float u, int n, int wrap)
+{
+    float p = u * (float)n;
+    int c = (int)floorf(p);
+    if (wrap == ORC_WRAP_REPEAT) { c %= n; if (c < 0) c += n; }
+    else { if (c < 0) c = 0; if (c > n - 1) c = n - 1; }
+    return c;
+}
+
+/* Cube-map face and face coordinates (standard major-axis mapping, faces
+ * +X,-X,+Y,-Y,+Z,-Z; ties prefer x, then y).  Float, in this order. */
+static int cube_face(const float d[3], float *u, float *v)
+{
+    float ax = fabsf(d[0]), ay = fabsf(d[1]), az = fabsf(d[2]);
+    int f;
+    float sc, tc, ma;
+    if (ax >= ay && ax >= az) {
+        ma = ax;
+        if (d[0] >= 0.0f) { f = 0; sc = -d[2]; tc = -d[1]; }
+        else { f = 1; sc = d[2]; tc = -d[1]; }
+    } else if (ay >= az) {
+        ma = ay;
+        if (d[1] >= 0.0f) { f = 2; sc = d[0]; tc = d[2]; }
+        else { f = 3; sc = d[0]; tc = -d[2]; }
+    } else {
+        ma = az;
+        if (d[2] >= 0.0f) { f = 4; sc = d[0]; tc = -d[1]; }
+        else { f = 5; sc = -d[0]; tc = -d[1]; }
+    }
+    if (!(ma > 0.0f)) return -1;
+    float us = sc / ma, vs = tc / ma;
+    *u = (us + 1.0f) * 0.5f;
+    *v = (vs + 1.0f) * 0.5f;
+    return f;
+}
+
+/* d(u,v)/d(direction) of the cube mapping for face f (double). */
+static void cube_face_jac(const float d[3], int f, double J[2][3])
+{
+    double x = d[0], y = d[1], z = d[2];
+    double sc, tc, ma;
+    int si, ti, mi;
+    double ss, ts, ms;
+    switch (f) {
+    case 0: sc = -z; tc = -y; ma = x; si = 2; ss = -1; ti = 1; ts = -1; mi = 0; ms = 1; break;
+    case 1: sc = z; tc = -y; ma = -x; si = 2; ss = 1; ti = 1; ts = -1; mi = 0; ms = -1; break;
+    case 2: sc = x; tc = z; ma = y; si = 0; ss = 1; ti = 2; ts = 1; mi = 1; ms = 1; break;
+    case 3: sc = x; tc = -z; ma = -y; si = 0; ss = 1; ti = 2; ts = -1; mi = 1; ms = -1; break;
+    case 4: sc = x; tc = -y; ma = z; si = 0; ss = 1; ti = 1; ts = -1; mi = 2; ms = 1; break;
+    default: sc = -x; tc = -y; ma = -z; si = 0; ss = -1; ti = 1; ts = -1; mi = 2; ms = -1; break;
+    }
+    memset(J, 0, sizeof(double) * 6);
+    /* u = (sc/ma + 1)/2 with ma = |major component| > 0 */
+    J[0][si] += 0.5 * ss / ma;
+    J[0][mi] += -0.5 * sc / (ma * ma) * ms;
+    J[1][ti] += 0.5 * ts / ma;
+    J[1][mi] += -0.5 * tc / (ma * ma) * ms;
+}
+
+typedef struct {
+    int ok;
+    int face;         /* 0 for 2D */
+    int x[2], y[2];   /* tap indices */
+    double fx, fy;
+    float u, v;       /* face / texture coordinates */
+} otap;
+
+static otap tex_taps(const orc_tex_desc *td, const float *coord)
+{
+    otap t;
+    memset(&t, 0, sizeof t);
+    float u, v;
+    int face = 0;
+    if (td->kind == ORC_TEX_CUBE) {
+        face = cube_face(coord, &u, &v);
+        if (face < 0) return t;
+        taps_1d(u, td->Wt, ORC_WRAP_CLAMP, &t.x[0], &t.x[1], &t.fx);
+        taps_1d(v, td->Ht, ORC_WRAP_CLAMP, &t.y[0], &t.y[1], &t.fy);
+    } else {
+        u = coord[0];
+        v = coord[1];
+        taps_1d(u, td->Wt, td->wrap_u, &t.x[0], &t.x[1], &t.fx);
+        taps_1d(v, td->Ht, td->wrap_v, &t.y[0], &t.y[1], &t.fy);
+    }
+    t.face = face;
+    t.u = u;
+    t.v = v;
+    t.ok = 1;
+    return t;
+}
+
+static const double *texel(const orc_tex_desc *td, const double *tex, int f, int y, int x)
+{
+    return tex + ((((int64_t)f * td->Ht + y) * td->Wt) + x) * td->Ct;
+}
+
+int orc_texture(const double *tex, const orc_tex_desc *td, const float *coord,
+                const int32_t *tri_id, int64_t N, double *out)
+{
+    int cd = td->kind == ORC_TEX_CUBE ? 3 : 2;
+    int Ct = td->Ct;
+    for (int64_t i = 0; i < N; i++) {
+        double *y = out + i * Ct;
+        for (int c = 0; c < Ct; c++) y[c] = 0.0;
+        if (tri_id && tri_id[i] < 0) continue;
+        otap t = tex_taps(td, coord + i * cd);
+        if (!t.ok) continue;
+        double wx[2] = {1.0 - t.fx, t.fx}, wy[2] = {1.0 - t.fy, t.fy};
+        for (int a = 0; a < 2; a++)
+            for (int b = 0; b < 2; b++) {
+                const double *tx = texel(td, tex, t.face, t.y[a], t.x[b]);
+                for (int c = 0; c < Ct; c++) y[c] += wy[a] * wx[b] * tx[c];
+            }
+    }
+    return 0;
+}
+
+/* d out / d coord: derivative of the bilinear weights (piecewise; at f == 0
+ * the derivative of the cell starting at the tap, i.e. the upper cell). */
+int orc_texture_bwd_coord(const double *tex, const orc_tex_desc *td, const float *coord,
+                          const int32_t *tri_id, int64_t N, const double *grad_out,
+                          double *grad_coord)
+{
+    int cd = td->kind == ORC_TEX_CUBE ? 3 : 2;
+    int Ct = td->Ct;
+    for (int64_t i = 0; i < N; i++) {
+        double *gc = grad_coord + i * cd;
+        for (int j = 0; j < cd; j++) gc[j] = 0.0;
+        if (tri_id && tri_id[i] < 0) continue;
+        otap t = tex_taps(td, coord + i * cd);
+        if (!t.ok) continue;
+        const double *g = grad_out + i * Ct;
+        double du = 0.0, dv = 0.0;
+        for (int c = 0; c < Ct; c++) {
+            double t00 = texel(td, tex, t.face, t.y[0], t.x[0])[c];
+            double t01 = texel(td, tex, t.face, t.y[0], t.x[1])[c];
+            double t10 = texel(td, tex, t.face, t.y[1], t.x[0])[c];
+            double t11 = texel(td, tex, t.face, t.y[1], t.x[1])[c];
+            du += g[c] * ((1.0 - t.fy) * (t01 - t00) + t.fy * (t11 - t10));
+            dv += g[c] * ((1.0 - t.fx) * (t10 - t00) + t.fx * (t11 - t01));
+        }
+        du *= td->Wt;
+        dv *= td->Ht;
+        if (td->kind == ORC_TEX_CUBE) {
+            double J[2][3];
+            cube_face_jac(coord + i * cd, t.face, J);
+            for (int j = 0; j < 3; j++) gc[j] = du * J[0][j] + dv * J[1][j];
+        } else {
+            gc[0] = du;
+            gc[1] = dv;
+        }
+    }
+    return 0;
+}
+
+/* Inverse UV (Algorithm 1): for every covered pixel i in increasing order,
+ * store i at the texture cell its UV falls into.  A later pixel overwrites an
+ * earlier one, so each cell ends up holding the largest such pixel index (the
+ * paper's "last updated value").  One slice per (view, layer). */
+int orc_invuv_build(const orc_tex_desc *td, const float *coord, const int32_t *tri_id,
+                    int S, int64_t Npix, int32_t *inv)
+{
+    int cd = td->kind == ORC_TEX_CUBE ? 3 : 2;
+    int F = td->kind == ORC_TEX_CUBE ? 6 : 1;
+    int64_t cells = (int64_t)F * td->Ht * td->Wt;
+    for (int s = 0; s < S; s++) {
+        int32_t *iv = inv + (int64_t)s * cells;
+        for (int64_t c = 0; c < cells; c++) iv[c] = -1;
+        for (int64_t i = 0; i < Npix; i++) {
+            int64_t o = (int64_t)s * Npix + i;
+            if (tri_id[o] < 0) continue;
+            const float *q = coord + o * cd;
+            int f = 0, cx, cy;
+            if (td->kind == ORC_TEX_CUBE) {
+                float u, v;
+                f = cube_face(q, &u, &v);
+                if (f < 0) continue;
+                cx = cell_1d(u, td->Wt, ORC_WRAP_CLAMP);
+                cy = cell_1d(v, td->Ht, ORC_WRAP_CLAMP);
+            } else {
+                cx = cell_1d(q[0], td->Wt, td->wrap_u);
+                cy = cell_1d(q[1], td->Ht, td->wrap_v);
+            }
+            iv[((int64_t)f * td->Ht + cy) * td->Wt + cx] = (int32_t)i;
+        }
+    }
+    return 0;
+}
+
+/* Weight with which texel (ty,tx) is a tap of sample t (taps can coincide
+ * under clamping, their weights then add). */
+static double tap_weight(const otap *t, int ty, int tx)
+{
+    double wx[2] = {1.0 - t->fx, t->fx}, wy[2] = {1.0 - t->fy, t->fy};
+    double w = 0.0;
+    for (int a = 0; a < 2; a++)
+        for (int b = 0; b < 2; b++)
+            if (t->y[a] == ty && t->x[b] == tx) w += wy[a] * wx[b];
+    return w;
+}
+
+/* Texture gradient through the inverse UV: every texel looks at the distinct
+ * in-range cells of the 3x3 block around it in every slice, and takes the
+ * recorded pixel's gradient times its bilinear weight on this texel.  Every
+ * recorded pixel thus feeds all four of its taps; pixels that lost their cell
+ * deliver nothing (the method's approximation).  Summation order: slice, then
+ * cells row-major. */
+int orc_texture_bwd_tex(const orc_tex_desc *td, const float *coord, const int32_t *tri_id,
+                        int S, int64_t Npix, const double *grad_out, const int32_t *inv,
+                        double *grad_tex)
+{
+    int cd = td->kind == ORC_TEX_CUBE ? 3 : 2;
+    int F = td->kind == ORC_TEX_CUBE ? 6 : 1;
+    int Ht = td->Ht, Wt = td->Wt, Ct = td->Ct;
+    int wu = td->kind == ORC_TEX_CUBE ? ORC_WRAP_CLAMP : td->wrap_u;
+    int wv = td->kind == ORC_TEX_CUBE ? ORC_WRAP_CLAMP : td->wrap_v;
+    int64_t cells = (int64_t)F * Ht * Wt;
+    memset(grad_tex, 0, sizeof(double) * (size_t)cells * Ct);
+    for (int f = 0; f < F; f++)
+        for (int ty = 0; ty < Ht; ty++)
+            for (int tx = 0; tx < Wt; tx++) {
+                double *gt = grad_tex + (((int64_t)f * Ht + ty) * Wt + tx) * Ct;
+                for (int s = 0; s < S; s++) {
+                    const int32_t *iv = inv + (int64_t)s * cells;
+                    for (int dy = -1; dy <= 1; dy++) {
+                        int cy = ty + dy;
+                        if (wv == ORC_WRAP_REPEAT) cy = (cy % Ht + Ht) % Ht;
+                        else if (cy < 0 || cy >= Ht) continue;
+                        for (int dx = -1; dx <= 1; dx++) {
+                            int cx = tx + dx;
+                            if (wu == ORC_WRAP_REPEAT) cx = (cx % Wt + Wt) % Wt;
+                            else if (cx < 0 || cx >= Wt) continue;
+                            int32_t i = iv[((int64_t)f * Ht + cy) * Wt + cx];
+                            if (i < 0) continue;
+                            int64_t o = (int64_t)s * Npix + i;
+                            otap t = tex_taps(td, coord + o * cd);
+                            if (!t.ok || t.face != f) continue;
+                            double w = tap_weight(&t, ty, tx);
+                            if (w == 0.0) continue;
+                            const double *g = grad_out + o * Ct;
+                            for (int c = 0; c < Ct; c++) gt[c] += w * g[c];
+                        }
+                    }
+                }
+            }
+    return 0;
+}
+
+/* Exact adjoint of the bilinear sampler (S^T g, every pixel counted), used as
+ * a diagnostic and as the special case the inverse UV must equal when no two
+ * pixels share a cell. */
+int orc_texture_adjoint(const orc_tex_desc *td, const float *coord, const int32_t *tri_id,
+                        int64_t N, const double *grad_out, double *grad_tex)
+{
+    int cd = td->kind == ORC_TEX_CUBE ? 3 : 2;
+    int F = td->kind == ORC_TEX_CUBE ? 6 : 1;
+    int Ct = td->Ct;
+    memset(grad_tex, 0, sizeof(double) * (size_t)F * td->Ht * td->Wt * Ct);
+    for (int64_t i = 0; i < N; i++) {
+        if (tri_id && tri_id[i] < 0) continue;
+        otap t = tex_taps(td, coord + i * cd);
+        if (!t.ok) continue;
+        double wx[2] = {1.0 - t.fx, t.fx}, wy[2] = {1.0 - t.fy, t.fy};
+        for (int a = 0; a < 2; a++)
+            for (int b = 0; b < 2; b++) {
+                double *gt = grad_tex + ((((int64_t)t.face * td->Ht + t.y[a]) * td->Wt) + t.x[b]) * Ct;
+                for (int c = 0; c < Ct; c++) gt[c] += wy[a] * wx[b] * grad_out[i * Ct + c];
+            }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* HardSoftRas blending (§3.4.3, BuildBlend)                                 */
+/* ------------------------------------------------------------------------ */
+
+/* S^H: the front layer is present and hard.  Hardness travels in the sign bit
+ * of dist (+0 hard, -0 soft); without dist every fragment is hard. */
+static int front_hard(const int32_t *tri_id, const double *dist, int64_t o)
+{
+    if (tri_id[o] < 0) return 0;
+    if (!dist) return 1;
+    return !signbit(dist[o]);
+}
+
+/* Edge mask E: pixels of S^H that differ from an in-image 4-neighbour are
+ * boundary pixels (both sides of the silhouette); E dilates them by an
+ * L-infinity square of radius rho, with rho the largest integer below
+ * delta * W pixels (so delta*W = 1 pixel gives E = boundary, the AA mode). */
+int orc_edge_mask(const int32_t *tri_id, const double *dist, int B, int K, int H, int W,
+                  float delta, int mode, uint8_t *E)
+{
+    int64_t N = (int64_t)H * W;
+    uint8_t *sh = (uint8_t *)malloc((size_t)N);
+    uint8_t *bd = (uint8_t *)malloc((size_t)N);
+    if (!sh || !bd) { free(sh); free(bd); return -2; }
+    int rho;
+    if (mode == ORC_BLEND_AA) rho = 0;
+    else {
+        float dw = delta * (float)W;
+        rho = (int)ceilf(dw) - 1;
+    }
+    for (int b = 0; b < B; b++) {
+        for (int64_t p = 0; p < N; p++) sh[p] = (uint8_t)front_hard(tri_id, dist, (int64_t)b * K * N + p);
+        for (int y = 0; y < H; y++)
+            for (int x = 0; x < W; x++) {
+                int64_t p = (int64_t)y * W + x;
+                int e = 0;
+                if (x > 0 && sh[p - 1] != sh[p]) e = 1;
+                if (x < W - 1 && sh[p + 1] != sh[p]) e = 1;
+                if (y > 0 && sh[p - W] != sh[p]) e = 1;
+                if (y < H - 1 && sh[p + W] != sh[p]) e = 1;
+                bd[p] = (uint8_t)e;
+            }
+        for (int y = 0; y < H; y++)
+            for (int x = 0; x < W; x++) {
+                uint8_t e = 0;
+                if (mode == ORC_BLEND_SOFTRAS) e = 1;
+                else if (mode == ORC_BLEND_HARD) e = 0;
+                else if (rho >= 0) {
+                    for (int qy = y - rho; qy <= y + rho && !e; qy++) {
+                        if (qy < 0 || qy >= H) continue;
+                        for (int qx = x - rho; qx <= x + rho; qx++) {
+                            if (qx < 0 || qx >= W) continue;
+                            if (bd[(int64_t)qy * W + qx]) { e = 1; break; }
+                        }
+                    }
+                }
+                E[(int64_t)b * N + (int64_t)y * W + x] = e;
+            }
+    }
+    free(sh);
+    free(bd);
+    return 0;
+}
+
+static double sigmoid(double x) { return 1.0 / (1.0 + exp(-x)); }
+
+/* I = E I^e + (1-E) I^ne with
+ *   D_k = sigmoid(dist_k / sigma), w_k = D_k S_k,
+ *   I_c^e = sum w_k C_k / sum w_k   (background 0 when no layer is present),
+ *   I_c^ne = S^H C_1,  I_s^e = 1 - prod_k (1 - w_k),  I_s^ne = S^H.
+ * The listing's normalisation by the stencil count does not match the colour
+ * equation; the equation is followed. */
+int orc_softras(const double *color, const double *dist, const int32_t *tri_id,
+                int B, int K, int H, int W, int Cc, double sigma, float delta, int mode,
+                double *out_color, double *out_sil, uint8_t *E)
+{
+    int rc = orc_edge_mask(tri_id, dist, B, K, H, W, delta, mode, E);
+    if (rc) return rc;
+    int64_t N = (int64_t)H * W;
+    for (int b = 0; b < B; b++)
+        for (int64_t p = 0; p < N; p++) {
+            int64_t q = (int64_t)b * N + p;
+            double *oc = out_color + q * Cc;
+            int64_t o1 = (int64_t)b * K * N + p;
+            int sH = front_hard(tri_id, dist, o1);
+            if (!E[q]) {
+                for (int c = 0; c < Cc; c++) oc[c] = sH ? color[o1 * Cc + c] : 0.0;
+                out_sil[q] = sH ? 1.0 : 0.0;
+                continue;
+            }
+            double Wsum = 0.0, prod = 1.0;
+            int nS = 0;
+            for (int c = 0; c < Cc; c++) oc[c] = 0.0;
+            for (int k = 0; k < K; k++) {
+                int64_t o = ((int64_t)b * K + k) * N + p;
+                if (tri_id[o] < 0) continue;
+                double d = dist ? dist[o] : 0.0;
+                double w = sigmoid(d / sigma);
+                nS++;
+                Wsum += w;
+                prod *= (1.0 - w);
+                for (int c = 0; c < Cc; c++) oc[c] += w * color[o * Cc + c];
+            }
+            for (int c = 0; c < Cc; c++) oc[c] = nS > 0 ? oc[c] / Wsum : 0.0;
+            out_sil[q] = 1.0 - prod;
+        }
+    return 0;
+}
+
+int orc_softras_bwd(const double *color, const double *dist, const int32_t *tri_id,
+                    int B, int K, int H, int W, int Cc, double sigma, const uint8_t *E,
+                    const double *grad_color, const double *grad_sil,
+                    double *grad_layer_color, double *grad_dist)
+{
+    int64_t N = (int64_t)H * W;
+    memset(grad_layer_color, 0, sizeof(double) * (size_t)B * K * N * Cc);
+    if (grad_dist) memset(grad_dist, 0, sizeof(double) * (size_t)B * K * N);
+    for (int b = 0; b < B; b++)
+        for (int64_t p = 0; p < N; p++) {
+            int64_t q = (int64_t)b * N + p;
+            int64_t o1 = (int64_t)b * K * N + p;
+            const double *gc = grad_color + q * Cc;
+            double gs = grad_sil ? grad_sil[q] : 0.0;
+            if (!E[q]) {
+                if (front_hard(tri_id, dist, o1))
+                    for (int c = 0; c < Cc; c++) grad_layer_color[o1 * Cc + c] = gc[c];
+                continue;
+            }
+            double w[5] = {0}, D[5] = {0}, Wsum = 0.0;
+            int S[5] = {0}, nS = 0;
+            for (int k = 0; k < K; k++) {
+                int64_t o = ((int64_t)b * K + k) * N + p;
+                if (tri_id[o] < 0) continue;
+                S[k] = 1;
+                nS++;
+                D[k] = sigmoid((dist ? dist[o] : 0.0) / sigma);
+                w[k] = D[k];
+                Wsum += w[k];
+            }
+            if (nS == 0) continue;
+            double Ic[16];
+            for (int c = 0; c < Cc; c++) {
+                Ic[c] = 0.0;
+                for (int k = 0; k < K; k++)
+                    if (S[k]) Ic[c] += w[k] * color[(((int64_t)b * K + k) * N + p) * Cc + c];
+                Ic[c] /= Wsum;
+            }
+            for (int k = 0; k < K; k++) {
+                if (!S[k]) continue;
+                int64_t o = ((int64_t)b * K + k) * N + p;
+                double gw = 0.0;
+                for (int c = 0; c < Cc; c++) {
+                    grad_layer_color[o * Cc + c] = gc[c] * w[k] / Wsum;
+                    gw += gc[c] * (color[o * Cc + c] - Ic[c]) / Wsum;
+                }
+                double others = 1.0;
+                for (int j = 0; j < K; j++)
+                    if (j != k && S[j]) others *= (1.0 - w[j]);
+                gw += gs * others;
+                if (grad_dist) grad_dist[o] = gw * D[k] * (1.0 - D[k]) / sigma;
+            }
+        }
+    return 0;
+}
