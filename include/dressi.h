@@ -1,0 +1,193 @@
+/*
+ * dressi.h — C ABI of libdressi.so, the gfx950 (MI355X) implementation of the
+ * rasterization hot path of the differentiable renderer "Dressi"
+ * (Eurographics 2022): rasterization with HardSoftRas soft coverage,
+ * perspective-correct attribute interpolation, bilinear texture sampling,
+ * the HardSoftRas blend, and the backward of each.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Every array argument is a DEVICE pointer to caller-owned, contiguous,
+ *   row-major memory of the dtype stated (float = IEEE binary32, int32_t,
+ *   uint8_t).  The library never frees, keeps or reallocates caller memory.
+ * - Per-pixel planes are laid out [B,K,H,W(,c)]: view b, layer k, row y (row 0
+ *   at the top of the image), column x.  Pixel (x,y) is sampled at its centre
+ *   (x + 1/2, y + 1/2).  Clip coordinates are (x,y,z,w) with x/w, y/w in [-1,1]
+ *   across the viewport (y up) and z/w in [0,1] between near and far.
+ * - Outputs and gradient outputs are fully OVERWRITTEN (never accumulated).
+ * - `stream` is a hipStream_t (NULL = the default stream).  Every call only
+ *   enqueues work on it and returns without waiting; it performs no host
+ *   synchronisation and no allocation once the context holds enough scratch
+ *   (dressi_reserve), so calls can be captured into a hipGraph.  Calls that
+ *   share a context must be issued on one stream (they share its scratch).
+ * - Return value: DRESSI_OK or a negative status; dressi_last_error() gives a
+ *   message.  Errors are detected on the host (arguments, scratch) before any
+ *   launch; a rejected call launches nothing.  Bin-capacity overflow can only
+ *   be seen on the device: it is recorded there and reported by
+ *   dressi_check_status(), and the affected outputs are then invalid.
+ *
+ * Paper references name sections, equations and algorithms of the paper.
+ */
+#ifndef DRESSI_H
+#define DRESSI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DRESSI_OK 0
+#define DRESSI_EINVAL (-1)    /* bad argument (null pointer, shape, range)   */
+#define DRESSI_ENOMEM (-2)    /* scratch too small while capturing / no mem  */
+#define DRESSI_EHIP (-3)      /* a HIP runtime call or launch failed         */
+#define DRESSI_EOVERFLOW (-4) /* device-side bin capacity exceeded           */
+
+/* texture kinds and wrap modes */
+#define DRESSI_TEX_2D 0   /* tex [Ht,Wt,Ct], coord (u,v); u along columns, v along rows */
+#define DRESSI_TEX_CUBE 1 /* tex [6,S,S,Ct] faces +X,-X,+Y,-Y,+Z,-Z; coord = direction */
+#define DRESSI_WRAP_REPEAT 0
+#define DRESSI_WRAP_CLAMP 1
+
+/* blend modes of the HardSoftRas blend (§3.4.3) */
+#define DRESSI_BLEND_HSR 0     /* edge mask from S^H, dilated to width delta       */
+#define DRESSI_BLEND_AA 1      /* edge mask = silhouette boundary (delta = 1 pixel) */
+#define DRESSI_BLEND_SOFTRAS 2 /* edge mask = 1 everywhere                         */
+#define DRESSI_BLEND_HARD 3    /* edge mask = 0: I = S^H C_1, alpha = S^H           */
+
+typedef struct dressi_ctx dressi_ctx;
+
+typedef struct {
+    int kind;           /* DRESSI_TEX_2D or DRESSI_TEX_CUBE (then Ht == Wt == S) */
+    int Ht, Wt, Ct;     /* texels per column, per row, channels (1..16)          */
+    int wrap_u, wrap_v; /* 2D only; repeat needs Wt (Ht) >= 3                     */
+} dressi_tex_desc;
+
+/* ----------------------------------------------------------------------------
+ * Context.  Owns only scratch memory (setup records, tile bins, per-tile
+ * fragment lists, inverse-UV slices, adjacency lists) and a small device
+ * status word.  One context per device and stream.
+ * ------------------------------------------------------------------------- */
+int dressi_create(dressi_ctx **ctx, int device);
+int dressi_destroy(dressi_ctx *ctx);
+const char *dressi_last_error(const dressi_ctx *ctx);
+/* Grow scratch to at least `bytes` and the tile-bin capacity to at least
+ * `bin_entries` (pass 0 to leave either unchanged).  Synchronises the device. */
+int dressi_reserve(dressi_ctx *ctx, size_t bytes, int64_t bin_entries);
+/* Bytes of scratch the given call shapes need (for dressi_reserve before a
+ * graph capture).  Pass the largest shapes of the step. */
+size_t dressi_scratch_bytes(int B, int V, int T, int H, int W, int K, float r,
+                            int Va, int C, int64_t tex_cells, int tex_slices);
+/* Waits for `stream`, then returns DRESSI_EOVERFLOW (and clears the flag) if a
+ * rasterization since the last check overflowed the bin capacity; *needed
+ * receives the capacity that call required (may be NULL). */
+int dressi_check_status(dressi_ctx *ctx, int64_t *needed, void *stream);
+
+/* ----------------------------------------------------------------------------
+ * Rasterization (Algorithm 2, §3.4.2; the Shift equation; PeelDepth).
+ *
+ * pos_clip [B,V,4] float: clip-space vertices of view b.  tris [T,3] int32:
+ * vertex indices, shared by all views.  K in 1..5 layers, r in [0,1]: soft
+ * reach in screen units (pixels / W); r = 0 rasterizes hard coverage only.
+ * cull: 0 = none, 1 = drop faces that are clockwise in NDC.
+ *
+ * Triangles are snapped to 1/256 pixel.  A pixel is hard-covered under the
+ * top-left fill rule with depth key 0.5*z/w (fragments with z/w outside (0,1)
+ * are dropped); when r > 0 a pixel not hard-covered whose distance to the
+ * triangle is <= r gets a soft fragment with key 0.5 + 0.5*distance.  Layer k
+ * of a pixel holds the k-th smallest distinct key, and the smallest triangle
+ * id at that key.  Outputs:
+ *   tri_id [B,K,H,W] int32  triangle index, -1 for an empty layer;
+ *   bary   [B,K,H,W,2] float perspective-correct barycentrics of corners 0,1
+ *          (corner 2 = 1 - b0 - b1; soft fragments extrapolate), 0 if empty;
+ *   dist   [B,K,H,W] float  signed distance to the triangle in screen units,
+ *          + for hard and - for soft fragments (the sign bit carries the
+ *          flag, also at 0), 0 if empty.  Required iff r > 0, else may be NULL.
+ * Limits: T < 2^21 - 1, |vertex| within a +-16384-pixel guard band, w > 0
+ * for all three vertices of a rasterized triangle (others are dropped).
+ * ------------------------------------------------------------------------- */
+int dressi_rasterize(dressi_ctx *ctx, const float *pos_clip, const int32_t *tris,
+                     int B, int V, int T, int H, int W, int K, float r, int cull,
+                     int32_t *tri_id, float *bary, float *dist, void *stream);
+
+/* Backward of dressi_rasterize with frozen visibility: the gradients of bary
+ * and dist carried to the clip-space vertices (Rasterize and PeelDepth have no
+ * backward of their own; snapping is treated as the identity).  grad_bary
+ * [B,K,H,W,2], grad_dist [B,K,H,W] (NULL = zero), tri_id from the forward.
+ * Output grad_pos_clip [B,V,4] (the z component is 0).  Deterministic:
+ * fragments are sorted by triangle id per tile and reduced in a fixed order. */
+int dressi_rasterize_bwd(dressi_ctx *ctx, const float *pos_clip, const int32_t *tris,
+                         int B, int V, int T, int H, int W, int K, float r, int cull,
+                         const int32_t *tri_id, const float *grad_bary, const float *grad_dist,
+                         float *grad_pos_clip, void *stream);
+
+/* ----------------------------------------------------------------------------
+ * Attribute interpolation (BuildInterpolate, appendix listing):
+ *   out[b,k,y,x,:] = b0*attr[a0] + b1*attr[a1] + (1-b0-b1)*attr[a2],
+ * (a0,a1,a2) = attr_tris[tri_id], 0 where tri_id < 0.  attr [Ba,Va,C] with
+ * Ba = 1 (shared by all views) or Ba = B.  attr_tris [T,3] may differ from the
+ * raster triangles (e.g. split UV seams).  C in 1..64.
+ * ------------------------------------------------------------------------- */
+int dressi_interpolate(dressi_ctx *ctx, const float *attr, int Ba, int Va, int C,
+                       const int32_t *attr_tris, int T, const int32_t *tri_id,
+                       const float *bary, int B, int K, int H, int W, float *out, void *stream);
+
+/* grad_attr [Ba,Va,C] (summed over views when Ba = 1) and grad_bary
+ * [B,K,H,W,2]; either may be NULL.  Deterministic (sorted per-tile lists). */
+int dressi_interpolate_bwd(dressi_ctx *ctx, const float *attr, int Ba, int Va, int C,
+                           const int32_t *attr_tris, int T, const int32_t *tri_id,
+                           const float *bary, int B, int K, int H, int W,
+                           const float *grad_out, float *grad_attr, float *grad_bary,
+                           void *stream);
+
+/* ----------------------------------------------------------------------------
+ * Bilinear texture sampling (the sampler behind GLSL texture(), §3.3.2).
+ * coord [S,H,W,2] (u,v) for 2D or [S,H,W,3] directions for cube maps, one
+ * slice per (view, layer); tri_id [S,H,W] masks empty pixels (output 0).
+ * Texel coordinates s = u*Wt - 1/2, t = v*Ht - 1/2; taps floor(s)+{0,1},
+ * floor(t)+{0,1} wrapped (repeat) or clamped.  out [S,H,W,Ct].
+ * ------------------------------------------------------------------------- */
+int dressi_texture(dressi_ctx *ctx, const float *tex, const dressi_tex_desc *td,
+                   const float *coord, const int32_t *tri_id, int S, int H, int W,
+                   float *out, void *stream);
+
+/* Backward.  grad_coord [S,H,W,2|3]: analytic derivative of the bilinear
+ * weights (and of the cube face mapping).  grad_tex [(6,)Ht,Wt,Ct]: the
+ * paper's inverse-UV texture (Algorithm 1): per slice, each texel cell keeps
+ * the largest covered pixel index whose coordinate falls in it; every texel
+ * then gathers, from the distinct in-range cells of its 3x3 neighbourhood in
+ * every slice, the kept pixel's gradient times that pixel's bilinear weight on
+ * the texel.  Integer atomicMax on pixel indices only, no float atomics; the
+ * sum runs over slices, then cells in row-major order.  Either output may be
+ * NULL.  Needs Ht, Wt >= 3 for repeat wrap. */
+int dressi_texture_bwd(dressi_ctx *ctx, const float *tex, const dressi_tex_desc *td,
+                       const float *coord, const int32_t *tri_id, int S, int H, int W,
+                       const float *grad_out, float *grad_tex, float *grad_coord, void *stream);
+
+/* ----------------------------------------------------------------------------
+ * HardSoftRas blend (§3.4.3, BuildBlend):
+ *   D_k = sigmoid(dist_k / sigma), w_k = D_k [tri_id_k >= 0],
+ *   I_c^e = sum w_k C_k / sum w_k (0 if no layer), I_s^e = 1 - prod (1 - w_k),
+ *   I_c = E I_c^e + (1 - E) S^H C_1,  I_s = E I_s^e + (1 - E) S^H,
+ * S^H = front layer present and hard (sign bit of dist; all hard if dist is
+ * NULL).  E: silhouette boundary of S^H (pixels with a differing in-image
+ * 4-neighbour) dilated by an L-infinity square of radius ceil(delta*W) - 1.
+ * color [B,K,H,W,Cc] (Cc 1..16) -> out_color [B,H,W,Cc], out_sil [B,H,W],
+ * edge_mask [B,H,W] uint8 (kept for the backward).
+ * ------------------------------------------------------------------------- */
+int dressi_softras(dressi_ctx *ctx, const float *color, const float *dist, const int32_t *tri_id,
+                   int B, int K, int H, int W, int Cc, float sigma, float delta, int mode,
+                   float *out_color, float *out_sil, uint8_t *edge_mask, void *stream);
+
+/* grad_layer_color [B,K,H,W,Cc], grad_dist [B,K,H,W] (NULL allowed);
+ * grad_sil may be NULL (zero). */
+int dressi_softras_bwd(dressi_ctx *ctx, const float *color, const float *dist,
+                       const int32_t *tri_id, int B, int K, int H, int W, int Cc, float sigma,
+                       const uint8_t *edge_mask, const float *grad_color, const float *grad_sil,
+                       float *grad_layer_color, float *grad_dist, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DRESSI_H */

@@ -1,0 +1,279 @@
+"""ctypes binding of libdressi.so: argument marshalling only.
+
+Each function has the name of the C entry point it calls, takes torch tensors
+that already live on the GPU (contiguous, dtype as the C header states),
+allocates the outputs with torch, and enqueues the call on torch's current
+stream.  All computation happens in the HIP kernels of libdressi.so; there is
+no CPU or PyTorch fallback: if the library is missing this module raises on
+import.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import threading
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdressi.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"libdressi.so not found at {LIB_PATH}; build it first "
+        "(python -c 'import __graft_entry__ as g; g.build()' or python paper_2204_01386_amd/build.py)")
+
+_lib = C.CDLL(LIB_PATH)
+
+TEX_2D, TEX_CUBE = 0, 1
+WRAP_REPEAT, WRAP_CLAMP = 0, 1
+BLEND_HSR, BLEND_AA, BLEND_SOFTRAS, BLEND_HARD = 0, 1, 2, 3
+
+STATUS = {0: "ok", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "EOVERFLOW"}
+
+
+class TexDesc(C.Structure):
+    _fields_ = [("kind", C.c_int), ("Ht", C.c_int), ("Wt", C.c_int), ("Ct", C.c_int),
+                ("wrap_u", C.c_int), ("wrap_v", C.c_int)]
+
+
+_vp, _i, _f, _i64, _sz = C.c_void_p, C.c_int, C.c_float, C.c_int64, C.c_size_t
+_SIG = {
+    "dressi_create": [C.POINTER(C.c_void_p), _i],
+    "dressi_destroy": [_vp],
+    "dressi_reserve": [_vp, _sz, _i64],
+    "dressi_check_status": [_vp, C.POINTER(C.c_int64), _vp],
+    "dressi_rasterize": [_vp, _vp, _vp, _i, _i, _i, _i, _i, _i, _f, _i, _vp, _vp, _vp, _vp],
+    "dressi_rasterize_bwd": [_vp, _vp, _vp, _i, _i, _i, _i, _i, _i, _f, _i, _vp, _vp, _vp, _vp, _vp],
+    "dressi_interpolate": [_vp, _vp, _i, _i, _i, _vp, _i, _vp, _vp, _i, _i, _i, _i, _vp, _vp],
+    "dressi_interpolate_bwd": [_vp, _vp, _i, _i, _i, _vp, _i, _vp, _vp, _i, _i, _i, _i, _vp, _vp,
+                               _vp, _vp],
+    "dressi_texture": [_vp, _vp, C.POINTER(TexDesc), _vp, _vp, _i, _i, _i, _vp, _vp],
+    "dressi_texture_bwd": [_vp, _vp, C.POINTER(TexDesc), _vp, _vp, _i, _i, _i, _vp, _vp, _vp, _vp],
+    "dressi_softras": [_vp, _vp, _vp, _vp, _i, _i, _i, _i, _i, _f, _f, _i, _vp, _vp, _vp, _vp],
+    "dressi_softras_bwd": [_vp, _vp, _vp, _vp, _i, _i, _i, _i, _i, _f, _vp, _vp, _vp, _vp, _vp, _vp],
+}
+for _name, _args in _SIG.items():
+    fn = getattr(_lib, _name)
+    fn.argtypes = _args
+    fn.restype = C.c_int
+_lib.dressi_last_error.argtypes = [_vp]
+_lib.dressi_last_error.restype = C.c_char_p
+_lib.dressi_scratch_bytes.argtypes = [_i, _i, _i, _i, _i, _i, _f, _i, _i, _i64, _i]
+_lib.dressi_scratch_bytes.restype = C.c_size_t
+
+EXPORTED = sorted(list(_SIG) + ["dressi_last_error", "dressi_scratch_bytes"])
+
+
+class DressiError(RuntimeError):
+    pass
+
+
+class Context:
+    """One libdressi context (scratch arena) per device."""
+
+    def __init__(self, device: int):
+        self.device = device
+        h = C.c_void_p()
+        rc = _lib.dressi_create(C.byref(h), device)
+        if rc != 0:
+            raise DressiError(f"dressi_create failed ({STATUS.get(rc, rc)})")
+        self.handle = h
+
+    def check(self, rc, what):
+        if rc != 0:
+            msg = _lib.dressi_last_error(self.handle).decode()
+            raise DressiError(f"{what}: {STATUS.get(rc, rc)}: {msg}")
+
+    def reserve(self, nbytes: int = 0, bin_entries: int = 0):
+        self.check(_lib.dressi_reserve(self.handle, nbytes, bin_entries), "dressi_reserve")
+
+    def check_status(self, stream=None):
+        needed = C.c_int64(0)
+        s = _stream(stream)
+        rc = _lib.dressi_check_status(self.handle, C.byref(needed), s)
+        if rc == -4:
+            return int(needed.value)
+        self.check(rc, "dressi_check_status")
+        return 0
+
+
+_ctx_lock = threading.Lock()
+_ctxs: dict[int, Context] = {}
+
+
+def context(device=None) -> Context:
+    d = torch.cuda.current_device() if device is None else int(device)
+    with _ctx_lock:
+        if d not in _ctxs:
+            _ctxs[d] = Context(d)
+        return _ctxs[d]
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    return C.c_void_p(t.data_ptr())
+
+
+def _need(t, dtype, name):
+    if not t.is_cuda:
+        raise DressiError(f"{name} must be a GPU tensor")
+    if t.dtype != dtype:
+        raise DressiError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise DressiError(f"{name} must be contiguous")
+    return t
+
+
+def scratch_bytes(B, V, T, H, W, K, r, Va=0, C_=0, tex_cells=0, tex_slices=0):
+    return int(_lib.dressi_scratch_bytes(B, V, T, H, W, K, float(r), Va, C_, tex_cells, tex_slices))
+
+
+# ---------------------------------------------------------------------------
+def dressi_rasterize(pos_clip, tris, H, W, K=1, r=0.0, cull=0):
+    _need(pos_clip, torch.float32, "pos_clip")
+    _need(tris, torch.int32, "tris")
+    B, V, _ = pos_clip.shape
+    T = tris.shape[0]
+    dev = pos_clip.device
+    tri_id = torch.empty((B, K, H, W), dtype=torch.int32, device=dev)
+    bary = torch.empty((B, K, H, W, 2), dtype=torch.float32, device=dev)
+    dist = torch.empty((B, K, H, W), dtype=torch.float32, device=dev) if r > 0 else None
+    ctx = context(dev.index)
+    ctx.check(_lib.dressi_rasterize(ctx.handle, _ptr(pos_clip), _ptr(tris), B, V, T, H, W, K,
+                                    float(r), int(cull), _ptr(tri_id), _ptr(bary), _ptr(dist),
+                                    _stream()), "dressi_rasterize")
+    return tri_id, bary, dist
+
+
+def dressi_rasterize_bwd(pos_clip, tris, tri_id, grad_bary, grad_dist=None, r=0.0, cull=0):
+    _need(pos_clip, torch.float32, "pos_clip")
+    _need(tris, torch.int32, "tris")
+    _need(tri_id, torch.int32, "tri_id")
+    _need(grad_bary, torch.float32, "grad_bary")
+    if grad_dist is not None:
+        _need(grad_dist, torch.float32, "grad_dist")
+    B, V, _ = pos_clip.shape
+    _, K, H, W = tri_id.shape
+    g = torch.empty_like(pos_clip)
+    ctx = context(pos_clip.device.index)
+    ctx.check(_lib.dressi_rasterize_bwd(ctx.handle, _ptr(pos_clip), _ptr(tris), B, V, tris.shape[0],
+                                        H, W, K, float(r), int(cull), _ptr(tri_id), _ptr(grad_bary),
+                                        _ptr(grad_dist), _ptr(g), _stream()), "dressi_rasterize_bwd")
+    return g
+
+
+def _attr3(attr):
+    return attr if attr.dim() == 3 else attr.unsqueeze(0)
+
+
+def dressi_interpolate(attr, attr_tris, tri_id, bary):
+    a = _need(_attr3(attr), torch.float32, "attr")
+    _need(attr_tris, torch.int32, "attr_tris")
+    _need(tri_id, torch.int32, "tri_id")
+    _need(bary, torch.float32, "bary")
+    Ba, Va, Cc = a.shape
+    B, K, H, W = tri_id.shape
+    out = torch.empty((B, K, H, W, Cc), dtype=torch.float32, device=a.device)
+    ctx = context(a.device.index)
+    ctx.check(_lib.dressi_interpolate(ctx.handle, _ptr(a), Ba, Va, Cc, _ptr(attr_tris),
+                                      attr_tris.shape[0], _ptr(tri_id), _ptr(bary), B, K, H, W,
+                                      _ptr(out), _stream()), "dressi_interpolate")
+    return out
+
+
+def dressi_interpolate_bwd(attr, attr_tris, tri_id, bary, grad_out, need_attr=True, need_bary=True):
+    a = _need(_attr3(attr), torch.float32, "attr")
+    _need(grad_out, torch.float32, "grad_out")
+    Ba, Va, Cc = a.shape
+    B, K, H, W = tri_id.shape
+    ga = torch.empty_like(a) if need_attr else None
+    gb = torch.empty_like(bary) if need_bary else None
+    ctx = context(a.device.index)
+    ctx.check(_lib.dressi_interpolate_bwd(ctx.handle, _ptr(a), Ba, Va, Cc, _ptr(attr_tris),
+                                          attr_tris.shape[0], _ptr(tri_id), _ptr(bary), B, K, H, W,
+                                          _ptr(grad_out), _ptr(ga), _ptr(gb), _stream()),
+              "dressi_interpolate_bwd")
+    if ga is not None and attr.dim() == 2:
+        ga = ga[0]
+    return ga, gb
+
+
+def _desc(tex, kind, wrap_u, wrap_v):
+    if kind == TEX_CUBE:
+        _, Ht, Wt, Ct = tex.shape
+    else:
+        Ht, Wt, Ct = tex.shape
+    return TexDesc(kind, Ht, Wt, Ct, wrap_u, wrap_v)
+
+
+def dressi_texture(tex, coord, tri_id, kind=TEX_2D, wrap_u=WRAP_REPEAT, wrap_v=WRAP_CLAMP):
+    """coord [S,H,W,2|3], tri_id [S,H,W] (or [B,K,H,W] flattened to S=B*K)."""
+    _need(tex, torch.float32, "tex")
+    _need(coord, torch.float32, "coord")
+    d = _desc(tex, kind, wrap_u, wrap_v)
+    lead = coord.shape[:-1]
+    H, W = lead[-2], lead[-1]
+    S = coord.numel() // (coord.shape[-1] * H * W)
+    out = torch.empty(lead + (d.Ct,), dtype=torch.float32, device=coord.device)
+    ctx = context(coord.device.index)
+    ctx.check(_lib.dressi_texture(ctx.handle, _ptr(tex), C.byref(d), _ptr(coord),
+                                  _ptr(tri_id) if tri_id is not None else None, S, H, W, _ptr(out),
+                                  _stream()), "dressi_texture")
+    return out
+
+
+def dressi_texture_bwd(tex, coord, tri_id, grad_out, kind=TEX_2D, wrap_u=WRAP_REPEAT,
+                       wrap_v=WRAP_CLAMP, need_tex=True, need_coord=True):
+    _need(grad_out, torch.float32, "grad_out")
+    d = _desc(tex, kind, wrap_u, wrap_v)
+    lead = coord.shape[:-1]
+    H, W = lead[-2], lead[-1]
+    S = coord.numel() // (coord.shape[-1] * H * W)
+    gt = torch.empty_like(tex) if need_tex else None
+    gc = torch.empty_like(coord) if need_coord else None
+    ctx = context(coord.device.index)
+    ctx.check(_lib.dressi_texture_bwd(ctx.handle, _ptr(tex), C.byref(d), _ptr(coord), _ptr(tri_id),
+                                      S, H, W, _ptr(grad_out), _ptr(gt), _ptr(gc), _stream()),
+              "dressi_texture_bwd")
+    return gt, gc
+
+
+def dressi_softras(color, dist, tri_id, sigma, delta, mode=BLEND_HSR):
+    _need(color, torch.float32, "color")
+    _need(tri_id, torch.int32, "tri_id")
+    if dist is not None:
+        _need(dist, torch.float32, "dist")
+    B, K, H, W = tri_id.shape
+    Cc = color.shape[-1]
+    dev = color.device
+    oc = torch.empty((B, H, W, Cc), dtype=torch.float32, device=dev)
+    os_ = torch.empty((B, H, W), dtype=torch.float32, device=dev)
+    E = torch.empty((B, H, W), dtype=torch.uint8, device=dev)
+    ctx = context(dev.index)
+    ctx.check(_lib.dressi_softras(ctx.handle, _ptr(color), _ptr(dist), _ptr(tri_id), B, K, H, W, Cc,
+                                  float(sigma), float(delta), int(mode), _ptr(oc), _ptr(os_), _ptr(E),
+                                  _stream()), "dressi_softras")
+    return oc, os_, E
+
+
+def dressi_softras_bwd(color, dist, tri_id, sigma, edge_mask, grad_color, grad_sil, need_dist=True):
+    _need(grad_color, torch.float32, "grad_color")
+    if grad_sil is not None:
+        _need(grad_sil, torch.float32, "grad_sil")
+    B, K, H, W = tri_id.shape
+    Cc = color.shape[-1]
+    gl = torch.empty_like(color)
+    gd = torch.empty_like(dist) if (dist is not None and need_dist) else None
+    ctx = context(color.device.index)
+    ctx.check(_lib.dressi_softras_bwd(ctx.handle, _ptr(color), _ptr(dist), _ptr(tri_id), B, K, H, W,
+                                      Cc, float(sigma), _ptr(edge_mask), _ptr(grad_color),
+                                      _ptr(grad_sil), _ptr(gl), _ptr(gd), _stream()),
+              "dressi_softras_bwd")
+    return gl, gd

@@ -1,0 +1,108 @@
+// Context, scratch arena and error reporting of libdressi.
+#include "dressi_internal.h"
+
+#include <cstdio>
+#include <new>
+
+int dressi_fail(dressi_ctx *ctx, int code, const std::string &msg) {
+    if (ctx) ctx->err = msg;
+    return code;
+}
+
+int dressi_hip_check(dressi_ctx *ctx, hipError_t e, const char *what) {
+    if (e == hipSuccess) return DRESSI_OK;
+    return dressi_fail(ctx, DRESSI_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+int dressi_launch_check(dressi_ctx *ctx, const char *what) {
+    return dressi_hip_check(ctx, hipGetLastError(), what);
+}
+
+extern "C" int dressi_create(dressi_ctx **out, int device) {
+    if (!out) return DRESSI_EINVAL;
+    *out = nullptr;
+    dressi_ctx *ctx = new (std::nothrow) dressi_ctx();
+    if (!ctx) return DRESSI_ENOMEM;
+    ctx->device = device;
+    hipError_t e = hipSetDevice(device);
+    if (e == hipSuccess) e = hipMalloc(&ctx->status, 4 * sizeof(int64_t));
+    if (e == hipSuccess) e = hipMemset(ctx->status, 0, 4 * sizeof(int64_t));
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        delete ctx;
+        return DRESSI_EHIP;
+    }
+    *out = ctx;
+    return DRESSI_OK;
+}
+
+extern "C" int dressi_destroy(dressi_ctx *ctx) {
+    if (!ctx) return DRESSI_OK;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    if (ctx->scratch) (void)hipFree(ctx->scratch);
+    if (ctx->status) (void)hipFree(ctx->status);
+    delete ctx;
+    return DRESSI_OK;
+}
+
+extern "C" const char *dressi_last_error(const dressi_ctx *ctx) {
+    return ctx ? ctx->err.c_str() : "null context";
+}
+
+static int grow(dressi_ctx *ctx, size_t bytes) {
+    if (bytes <= ctx->scratch_bytes) return DRESSI_OK;
+    size_t nb = bytes + bytes / 4 + (1 << 20);
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) return dressi_hip_check(ctx, e, "synchronize before scratch growth");
+    if (ctx->scratch) (void)hipFree(ctx->scratch);
+    ctx->scratch = nullptr;
+    ctx->scratch_bytes = 0;
+    e = hipMalloc(&ctx->scratch, nb);
+    if (e != hipSuccess) {
+        ctx->scratch = nullptr;
+        return dressi_fail(ctx, DRESSI_ENOMEM, "scratch allocation of " + std::to_string(nb) +
+                                                   " bytes failed: " + hipGetErrorString(e));
+    }
+    ctx->scratch_bytes = nb;
+    return DRESSI_OK;
+}
+
+int dressi_scratch(dressi_ctx *ctx, size_t bytes, hipStream_t stream) {
+    if (bytes <= ctx->scratch_bytes) return DRESSI_OK;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    hipError_t e = hipStreamIsCapturing(stream, &cs);
+    if (e != hipSuccess) return dressi_hip_check(ctx, e, "hipStreamIsCapturing");
+    if (cs != hipStreamCaptureStatusNone)
+        return dressi_fail(ctx, DRESSI_ENOMEM,
+                           "scratch too small during stream capture: need " + std::to_string(bytes) +
+                               " bytes, call dressi_reserve before capturing");
+    return grow(ctx, bytes);
+}
+
+extern "C" int dressi_reserve(dressi_ctx *ctx, size_t bytes, int64_t bin_entries) {
+    if (!ctx) return DRESSI_EINVAL;
+    if (bin_entries > ctx->bin_capacity) ctx->bin_capacity = bin_entries;
+    return grow(ctx, bytes);
+}
+
+extern "C" int dressi_check_status(dressi_ctx *ctx, int64_t *needed, void *stream) {
+    if (!ctx) return DRESSI_EINVAL;
+    int64_t h[4];
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipMemcpyAsync(h, ctx->status, sizeof h, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return dressi_hip_check(ctx, e, "reading device status");
+    if (needed) *needed = h[1];
+    if (h[0]) {
+        // clear with a tiny fill kernel rather than a memset (capture friendly)
+        dressi_fill_i32(reinterpret_cast<int32_t *>(ctx->status), 0, 8, s);
+        e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return dressi_hip_check(ctx, e, "clearing device status");
+        return dressi_fail(ctx, DRESSI_EOVERFLOW,
+                           "tile-bin capacity exceeded: " + std::to_string(h[1]) +
+                               " entries needed; call dressi_reserve and rerun");
+    }
+    return DRESSI_OK;
+}

@@ -1,0 +1,234 @@
+// Internal declarations of libdressi (gfx950).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "../../include/dressi.h"
+
+#define DRESSI_TILE 16          // screen tile edge in pixels (one lane per pixel)
+#define DRESSI_TILE_PIX 256     // pixels per tile
+#define DRESSI_MAX_K 5
+#define DRESSI_SUBPIX 256       // 8 sub-pixel bits
+
+struct dressi_ctx {
+    int device = 0;
+    void *scratch = nullptr;    // device arena, reused by every call on this context
+    size_t scratch_bytes = 0;
+    int64_t bin_capacity = 0;   // entries of the tile-bin array
+    int64_t *status = nullptr;  // device: [0] overflow flag, [1] entries needed
+    std::string err;
+};
+
+// ---------------------------------------------------------------------------
+// host helpers (context.hip)
+// ---------------------------------------------------------------------------
+int dressi_fail(dressi_ctx *ctx, int code, const std::string &msg);
+int dressi_hip_check(dressi_ctx *ctx, hipError_t e, const char *what);
+// Makes sure the arena holds `bytes`; grows it outside stream capture,
+// fails with DRESSI_ENOMEM while `stream` is capturing.
+int dressi_scratch(dressi_ctx *ctx, size_t bytes, hipStream_t stream);
+int dressi_launch_check(dressi_ctx *ctx, const char *what);
+
+// Bump allocator over the arena: carve(n) returns 256-byte aligned offsets.
+struct Carver {
+    size_t off = 0;
+    size_t take(size_t bytes) {
+        size_t o = off;
+        off += (bytes + 255) & ~size_t(255);
+        return o;
+    }
+};
+template <class T> static inline T *at(void *base, size_t off) {
+    return reinterpret_cast<T *>(static_cast<char *>(base) + off);
+}
+
+// ---------------------------------------------------------------------------
+// primitives (prims.hip)
+// ---------------------------------------------------------------------------
+void dressi_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
+void dressi_fill_f32(float *p, float v, int64_t n, hipStream_t s);
+// Exclusive scan of n int32 counts into out[0..n] (out[n] = total); `tmp`
+// needs dressi_scan_tmp_bytes(n).  out may alias nothing.
+size_t dressi_scan_tmp_bytes(int64_t n);
+void dressi_exclusive_scan(const int32_t *in, int32_t *out, int64_t n, void *tmp, hipStream_t s);
+
+// vertex -> corner adjacency: offsets [V+1], corners [3T] (corner = 3t+i)
+struct Adjacency {
+    int32_t *offsets;
+    int32_t *corners;
+};
+size_t dressi_adjacency_bytes(int V, int T);
+void dressi_build_adjacency(const int32_t *tris, int T, int V, void *scratch, Adjacency &adj,
+                            hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// per-tile fragment lists (raster.hip): fragments of each tile sorted by
+// triangle id, used by every deterministic backward reduction
+// ---------------------------------------------------------------------------
+struct FragLists {
+    int32_t *n_frag;    // [B*nTiles] valid fragments in the tile
+    int32_t *n_rec;     // [B*nTiles] distinct triangles in the tile
+    uint16_t *frag;     // [B*nTiles*256*K] local fragment index k*256 + pixel, sorted
+    int32_t *rec_tri;   // [B*nTiles*256*K] distinct triangle ids, ascending
+    int32_t *rec_start; // [B*nTiles*256*K] first sorted fragment of each triangle
+};
+size_t dressi_fraglists_bytes(int B, int H, int W, int K);
+void dressi_build_fraglists(const int32_t *tri_id, int B, int K, int H, int W, void *scratch,
+                            FragLists &fl, hipStream_t s);
+
+// transpose of the per-tile records: for every (view, triangle) the tiles in
+// which it has fragments, as (tile index b*nTiles+tile, record index) pairs in
+// ascending tile order
+struct TriTiles {
+    int32_t *offsets;   // [B*T+1]
+    int2 *entries;      // [total records]
+};
+size_t dressi_tritiles_bytes(int B, int T, int H, int W, int K);
+void dressi_build_tritiles(const FragLists &fl, int B, int T, int K, int H, int W, void *scratch,
+                           TriTiles &tt, hipStream_t s);
+
+__host__ __device__ static inline int tiles_x(int W) { return (W + DRESSI_TILE - 1) / DRESSI_TILE; }
+__host__ __device__ static inline int tiles_y(int H) { return (H + DRESSI_TILE - 1) / DRESSI_TILE; }
+
+// ---------------------------------------------------------------------------
+// Triangle setup shared by the forward and backward kernels (device code).
+// The arithmetic order below is the contract the oracle mirrors:
+//   x_px = (x/w + 1) * (W/2), y_px = (1 - y/w) * (H/2) in float, snapped with
+//   round-to-nearest-even to 1/256 px; twice the signed area in int64; the
+//   vertex order is normalised so the area is positive (1 <-> 2 swapped);
+//   zero area or a vertex with w <= 0 drops the triangle.
+// ---------------------------------------------------------------------------
+struct TriSetup {
+    int X[3], Y[3];   // snapped fixed-point coordinates, normalised order
+    float zn[3];      // z/w
+    float w[3];       // clip w
+    float Af;         // twice the area as float
+    int meta;         // bit0 valid, bits1-3 edge owns zero, bits 4-9 corner of vertex i
+    int box0, box1;   // pixel bbox: x0 | x1 << 16, y0 | y1 << 16 (hard or soft)
+};
+static_assert(sizeof(TriSetup) == 64, "setup record is one 64-byte line");
+
+__device__ __forceinline__ bool dr_snap(float c, float w, float half, bool is_y, int &out) {
+    float n = c / w;
+    float p = is_y ? (1.0f - n) * half : (n + 1.0f) * half;
+    float f = p * 256.0f;
+    if (!(fabsf(f) < 4194304.0f)) return false;
+    out = (int)rintf(f);
+    return true;
+}
+
+__device__ __forceinline__ int floor_div256(int v) { return v >> 8; }  // arithmetic shift floors
+
+// Builds the record of triangle `tv` (three vertex ids) for a view.  `margin`
+// extends the pixel bbox (soft reach).  cull = 1 drops faces clockwise in NDC.
+__device__ __forceinline__ TriSetup dr_setup(const float4 *pc, int v0, int v1, int v2, int H,
+                                             int W, int cull, int margin) {
+    TriSetup s;
+    s.meta = 0;
+    s.box0 = 1;      // empty box (x0 = 1 > x1 = 0)
+    s.box1 = 1;
+    const int vid[3] = {v0, v1, v2};
+    float4 p[3];
+    int X[3], Y[3];
+    float hw = 0.5f * (float)W, hh = 0.5f * (float)H;
+#pragma unroll
+    for (int i = 0; i < 3; i++) {
+        p[i] = pc[vid[i]];
+        if (!(p[i].w > 0.0f)) return s;
+        if (!dr_snap(p[i].x, p[i].w, hw, false, X[i])) return s;
+        if (!dr_snap(p[i].y, p[i].w, hh, true, Y[i])) return s;
+    }
+    int64_t A2 = (int64_t)(X[1] - X[0]) * (int64_t)(Y[2] - Y[0]) -
+                 (int64_t)(X[2] - X[0]) * (int64_t)(Y[1] - Y[0]);
+    if (A2 == 0) return s;
+    if (cull && A2 > 0) return s;
+    int o1 = 1, o2 = 2;
+    if (A2 < 0) { o1 = 2; o2 = 1; A2 = -A2; }
+    const int ord[3] = {0, o1, o2};
+    int xmin = 0x7fffffff, xmax = -0x7fffffff, ymin = 0x7fffffff, ymax = -0x7fffffff;
+#pragma unroll
+    for (int i = 0; i < 3; i++) {
+        int c = ord[i];
+        s.X[i] = X[c];
+        s.Y[i] = Y[c];
+        s.zn[i] = p[c].z / p[c].w;
+        s.w[i] = p[c].w;
+        s.meta |= c << (4 + 2 * i);
+        xmin = min(xmin, X[c]); xmax = max(xmax, X[c]);
+        ymin = min(ymin, Y[c]); ymax = max(ymax, Y[c]);
+    }
+    s.Af = (float)A2;
+#pragma unroll
+    for (int i = 0; i < 3; i++) {
+        int a = (i + 1) % 3, b = (i + 2) % 3;
+        int dx = s.X[b] - s.X[a], dy = s.Y[b] - s.Y[a];
+        if (dy < 0 || (dy == 0 && dx > 0)) s.meta |= 1 << (1 + i);
+    }
+    // pixels with centre 256x+128 inside [xmin, xmax]
+    int x0 = -floor_div256(-(xmin - 128)) - margin;   // ceil
+    int x1 = floor_div256(xmax - 128) + margin;
+    int y0 = -floor_div256(-(ymin - 128)) - margin;
+    int y1 = floor_div256(ymax - 128) + margin;
+    x0 = max(x0, 0); y0 = max(y0, 0);
+    x1 = min(x1, W - 1); y1 = min(y1, H - 1);
+    if (x0 > x1 || y0 > y1) return s;
+    s.box0 = x0 | (x1 << 16);
+    s.box1 = y0 | (y1 << 16);
+    s.meta |= 1;
+    return s;
+}
+
+__device__ __forceinline__ int dr_corner(int meta, int i) { return (meta >> (4 + 2 * i)) & 3; }
+
+// Edge function of the edge opposite vertex i at fixed-point (px, py).
+__device__ __forceinline__ int64_t dr_edge(const int *X, const int *Y, int i, int px, int py) {
+    int a = (i == 2) ? 0 : i + 1;
+    int b = (i == 0) ? 2 : i - 1;
+    return (int64_t)(X[b] - X[a]) * (int64_t)(py - Y[a]) -
+           (int64_t)(Y[b] - Y[a]) * (int64_t)(px - X[a]);
+}
+
+// Segment distance (fixed-point units, float) of edge i, from exact integers.
+__device__ __forceinline__ float dr_segdist(const int *X, const int *Y, int i, int px, int py,
+                                            int64_t E) {
+    int a = (i == 2) ? 0 : i + 1;
+    int b = (i == 0) ? 2 : i - 1;
+    int64_t ex = X[b] - X[a], ey = Y[b] - Y[a];
+    int64_t qx = px - X[a], qy = py - Y[a];
+    int64_t dot = qx * ex + qy * ey;
+    int64_t len2 = ex * ex + ey * ey;
+    if (dot <= 0) return sqrtf((float)(qx * qx + qy * qy));
+    if (dot >= len2) {
+        int64_t rx = px - X[b], ry = py - Y[b];
+        return sqrtf((float)(rx * rx + ry * ry));
+    }
+    int64_t ae = E < 0 ? -E : E;
+    return (float)ae / sqrtf((float)len2);
+}
+
+// Normalised distance (pixels / W) to the triangle and the nearest edge
+// (lowest index on ties).
+__device__ __forceinline__ float dr_distnorm(const int *X, const int *Y, int px, int py,
+                                             const int64_t *E, float scale, int &nearest) {
+    float best = dr_segdist(X, Y, 0, px, py, E[0]);
+    nearest = 0;
+    float d1 = dr_segdist(X, Y, 1, px, py, E[1]);
+    if (d1 < best) { best = d1; nearest = 1; }
+    float d2 = dr_segdist(X, Y, 2, px, py, E[2]);
+    if (d2 < best) { best = d2; nearest = 2; }
+    return best / scale;
+}
+
+__device__ __forceinline__ float dr_depth(const TriSetup &s, const int64_t *E) {
+    float l1 = (float)E[1] / s.Af;
+    float l2 = (float)E[2] / s.Af;
+    float d1 = s.zn[1] - s.zn[0];
+    float d2 = s.zn[2] - s.zn[0];
+    float t1 = l1 * d1;
+    float t2 = l2 * d2;
+    float z = s.zn[0] + t1;
+    return z + t2;
+}

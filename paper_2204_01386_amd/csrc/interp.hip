@@ -1,0 +1,212 @@
+// Attribute interpolation (BuildInterpolate) and its backward for gfx950.
+//
+// Forward: one lane per (pixel, layer) fragment; memory bound.
+// Backward: grad_bary is elementwise; grad_attr is a deterministic gather:
+// fragments are sorted per tile by triangle id (shared with the rasterizer
+// backward), each (view, triangle) walks its fragments through the
+// triangle->tile transpose and accumulates b_i * g for its three corners in
+// registers, then one thread per attribute vertex sums its corners in
+// ascending order.  No float atomics.
+#include "dressi_internal.h"
+
+#define IB_CH 16   // channels per pass of the per-triangle gather
+
+__global__ void k_interp(const float *__restrict__ attr, int Ba, int Va, int C,
+                         const int32_t *__restrict__ attr_tris, int T,
+                         const int32_t *__restrict__ tri_id, const float2 *__restrict__ bary,
+                         int64_t per_view, int64_t n, float *__restrict__ out) {
+    int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= n) return;
+    float *y = out + o * C;
+    int t = tri_id[o];
+    int v0 = -1, v1 = -1, v2 = -1;
+    if (t >= 0 && t < T) {
+        v0 = attr_tris[3 * (int64_t)t];
+        v1 = attr_tris[3 * (int64_t)t + 1];
+        v2 = attr_tris[3 * (int64_t)t + 2];
+    }
+    if (v0 < 0 || v0 >= Va || v1 < 0 || v1 >= Va || v2 < 0 || v2 >= Va) {
+        for (int c = 0; c < C; c++) y[c] = 0.0f;
+        return;
+    }
+    int b = (int)(o / per_view);
+    const float *a = attr + (Ba == 1 ? 0 : (int64_t)b * Va * C);
+    float2 w = bary[o];
+    float w2 = 1.0f - w.x - w.y;
+    const float *a0 = a + (int64_t)v0 * C, *a1 = a + (int64_t)v1 * C, *a2 = a + (int64_t)v2 * C;
+    for (int c = 0; c < C; c++) y[c] = w.x * a0[c] + w.y * a1[c] + w2 * a2[c];
+}
+
+static int check_interp(dressi_ctx *ctx, const void *attr, int Ba, int Va, int C, const void *at,
+                        int T, const void *tid, const void *bary, int B, int K, int H, int W) {
+    if (!ctx) return DRESSI_EINVAL;
+    if (B < 0 || K < 1 || K > DRESSI_MAX_K || H < 0 || W < 0 || T < 0 || Va < 0)
+        return dressi_fail(ctx, DRESSI_EINVAL, "interpolate: bad dimensions");
+    if (C < 1 || C > 64) return dressi_fail(ctx, DRESSI_EINVAL, "interpolate: C must be 1..64");
+    if (!(Ba == 1 || Ba == B)) return dressi_fail(ctx, DRESSI_EINVAL, "interpolate: Ba must be 1 or B");
+    if ((int64_t)B * K * H * W > 0 && (!attr || !at || !tid || !bary))
+        return dressi_fail(ctx, DRESSI_EINVAL, "interpolate: null input");
+    return DRESSI_OK;
+}
+
+extern "C" int dressi_interpolate(dressi_ctx *ctx, const float *attr, int Ba, int Va, int C,
+                                  const int32_t *attr_tris, int T, const int32_t *tri_id,
+                                  const float *bary, int B, int K, int H, int W, float *out,
+                                  void *stream) {
+    int rc = check_interp(ctx, attr, Ba, Va, C, attr_tris, T, tri_id, bary, B, K, H, W);
+    if (rc) return rc;
+    int64_t n = (int64_t)B * K * H * W;
+    if (n == 0) return DRESSI_OK;
+    if (!out) return dressi_fail(ctx, DRESSI_EINVAL, "interpolate: null out");
+    hipStream_t st = (hipStream_t)stream;
+    k_interp<<<(int)((n + 255) / 256), 256, 0, st>>>(attr, Ba, Va, C, attr_tris, T, tri_id,
+                                                     reinterpret_cast<const float2 *>(bary),
+                                                     (int64_t)K * H * W, n, out);
+    return dressi_launch_check(ctx, "interpolate");
+}
+
+// grad_bary: g . (a0 - a2), g . (a1 - a2)
+__global__ void k_interp_bwd_bary(const float *__restrict__ attr, int Ba, int Va, int C,
+                                  const int32_t *__restrict__ attr_tris, int T,
+                                  const int32_t *__restrict__ tri_id, int64_t per_view, int64_t n,
+                                  const float *__restrict__ grad_out, float2 *__restrict__ grad_bary) {
+    int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= n) return;
+    int t = tri_id[o];
+    int v0 = -1, v1 = -1, v2 = -1;
+    if (t >= 0 && t < T) {
+        v0 = attr_tris[3 * (int64_t)t];
+        v1 = attr_tris[3 * (int64_t)t + 1];
+        v2 = attr_tris[3 * (int64_t)t + 2];
+    }
+    if (v0 < 0 || v0 >= Va || v1 < 0 || v1 >= Va || v2 < 0 || v2 >= Va) {
+        grad_bary[o] = make_float2(0.0f, 0.0f);
+        return;
+    }
+    int b = (int)(o / per_view);
+    const float *a = attr + (Ba == 1 ? 0 : (int64_t)b * Va * C);
+    const float *a0 = a + (int64_t)v0 * C, *a1 = a + (int64_t)v1 * C, *a2 = a + (int64_t)v2 * C;
+    const float *g = grad_out + o * C;
+    float g0 = 0.0f, g1 = 0.0f;
+    for (int c = 0; c < C; c++) {
+        float gc = g[c];
+        g0 += gc * (a0[c] - a2[c]);
+        g1 += gc * (a1[c] - a2[c]);
+    }
+    grad_bary[o] = make_float2(g0, g1);
+}
+
+// per (view or shared, triangle, channel chunk): sum over fragments of b_i g
+__global__ void k_interp_bwd_tri(int B, int Ba, int T, int K, int H, int W, int C, int ntx, FragLists fl,
+                                 TriTiles tt, const float2 *__restrict__ bary,
+                                 const float *__restrict__ grad_out, float *__restrict__ corner_grad) {
+    int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int chunk = blockIdx.y;
+    const int c0 = chunk * IB_CH;
+    const int nc = min(IB_CH, C - c0);
+    if (gid >= (int64_t)Ba * T) return;
+    int ba = (int)(gid / T), t = (int)(gid - (int64_t)ba * T);
+    float acc[3][IB_CH];
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int c = 0; c < IB_CH; c++) acc[i][c] = 0.0f;
+    const int nt = ntx * tiles_y(H);
+    int b0 = (Ba == 1) ? 0 : ba, b1 = (Ba == 1) ? B : ba + 1;
+    for (int b = b0; b < b1; b++) {
+        int64_t key = (int64_t)b * T + t;
+        for (int e = tt.offsets[key]; e < tt.offsets[key + 1]; e++) {
+            int2 ent = tt.entries[e];
+            int64_t bt = ent.x;
+            int tile = (int)(bt - (int64_t)b * nt);
+            int tx = tile % ntx, ty = tile / ntx;
+            int64_t base = bt * DRESSI_TILE_PIX * K;
+            int r = ent.y;
+            int j0 = fl.rec_start[base + r];
+            int j1 = (r + 1 < fl.n_rec[bt]) ? fl.rec_start[base + r + 1] : fl.n_frag[bt];
+            for (int j = j0; j < j1; j++) {
+                int f = fl.frag[base + j];
+                int k = f >> 8, pl = f & 255;
+                int x = tx * DRESSI_TILE + (pl & 15), y = ty * DRESSI_TILE + (pl >> 4);
+                int64_t o = (((int64_t)b * K + k) * H + y) * W + x;
+                float2 w = bary[o];
+                float w2 = 1.0f - w.x - w.y;
+                const float *g = grad_out + o * C + c0;
+#pragma unroll
+                for (int c = 0; c < IB_CH; c++) {
+                    if (c < nc) {
+                        float gc = g[c];
+                        acc[0][c] += w.x * gc;
+                        acc[1][c] += w.y * gc;
+                        acc[2][c] += w2 * gc;
+                    }
+                }
+            }
+        }
+    }
+    float *cg = corner_grad + gid * 3 * C;
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int c = 0; c < IB_CH; c++)
+            if (c < nc) cg[i * C + c0 + c] = acc[i][c];
+}
+
+__global__ void k_interp_vertex_gather(const float *__restrict__ corner_grad, Adjacency adj, int Ba,
+                                       int Va, int T, int C, float *__restrict__ grad_attr) {
+    int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= (int64_t)Ba * Va * C) return;
+    int c = (int)(gid % C);
+    int64_t bv = gid / C;
+    int ba = (int)(bv / Va), v = (int)(bv - (int64_t)ba * Va);
+    const float *cgb = corner_grad + (int64_t)ba * T * 3 * C;
+    float s = 0.0f;
+    for (int j = adj.offsets[v]; j < adj.offsets[v + 1]; j++) {
+        int cr = adj.corners[j];
+        s += cgb[(int64_t)cr * C + c];   // corner cr = 3t + i -> [t][i][c]
+    }
+    grad_attr[gid] = s;
+}
+
+extern "C" int dressi_interpolate_bwd(dressi_ctx *ctx, const float *attr, int Ba, int Va, int C,
+                                      const int32_t *attr_tris, int T, const int32_t *tri_id,
+                                      const float *bary, int B, int K, int H, int W,
+                                      const float *grad_out, float *grad_attr, float *grad_bary,
+                                      void *stream) {
+    int rc = check_interp(ctx, attr, Ba, Va, C, attr_tris, T, tri_id, bary, B, K, H, W);
+    if (rc) return rc;
+    int64_t n = (int64_t)B * K * H * W;
+    if (n > 0 && !grad_out) return dressi_fail(ctx, DRESSI_EINVAL, "interpolate_bwd: null grad_out");
+    hipStream_t st = (hipStream_t)stream;
+    if (grad_bary && n > 0)
+        k_interp_bwd_bary<<<(int)((n + 255) / 256), 256, 0, st>>>(
+            attr, Ba, Va, C, attr_tris, T, tri_id, (int64_t)K * H * W, n, grad_out,
+            reinterpret_cast<float2 *>(grad_bary));
+    if (grad_attr && Va > 0) {
+        Carver c;
+        size_t o_fl = c.take(dressi_fraglists_bytes(B, H, W, K));
+        size_t o_tt = c.take(dressi_tritiles_bytes(B, T, H, W, K));
+        size_t o_adj = c.take(dressi_adjacency_bytes(Va, T));
+        size_t o_cg = c.take(sizeof(float) * 3 * (size_t)C * Ba * T);
+        rc = dressi_scratch(ctx, c.off, st);
+        if (rc) return rc;
+        void *S = ctx->scratch;
+        FragLists fl;
+        TriTiles tt;
+        Adjacency adj;
+        dressi_build_fraglists(tri_id, B, K, H, W, at<void>(S, o_fl), fl, st);
+        dressi_build_tritiles(fl, B, T, K, H, W, at<void>(S, o_tt), tt, st);
+        dressi_build_adjacency(attr_tris, T, Va, at<void>(S, o_adj), adj, st);
+        float *cg = at<float>(S, o_cg);
+        int64_t ntri = (int64_t)Ba * T;
+        if (ntri > 0) {
+            dim3 g((unsigned)((ntri + 127) / 128), (unsigned)((C + IB_CH - 1) / IB_CH));
+            k_interp_bwd_tri<<<g, 128, 0, st>>>(B, Ba, T, K, H, W, C, tiles_x(W), fl, tt,
+                                                 reinterpret_cast<const float2 *>(bary), grad_out, cg);
+        }
+        int64_t ng = (int64_t)Ba * Va * C;
+        k_interp_vertex_gather<<<(int)((ng + 255) / 256), 256, 0, st>>>(cg, adj, Ba, Va, T, C,
+                                                                          grad_attr);
+    }
+    return dressi_launch_check(ctx, "interpolate_bwd");
+}

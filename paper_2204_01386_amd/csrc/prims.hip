@@ -1,0 +1,203 @@
+// Small device primitives of libdressi: fills, a three-phase exclusive scan,
+// and the vertex -> corner adjacency used by the deterministic gathers.
+#include "dressi_internal.h"
+
+// ---------------------------------------------------------------------------
+// fills (used instead of hipMemsetAsync so every call stays graph-safe)
+// ---------------------------------------------------------------------------
+__global__ void k_fill_i32(int32_t *p, int32_t v, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) p[i] = v;
+}
+
+__global__ void k_fill_f32(float *p, float v, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) p[i] = v;
+}
+
+static int fill_grid(int64_t n) {
+    int64_t g = (n + 255) / 256;
+    if (g > 8192) g = 8192;
+    return g < 1 ? 1 : (int)g;
+}
+
+void dressi_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    k_fill_i32<<<fill_grid(n), 256, 0, s>>>(p, v, n);
+}
+
+void dressi_fill_f32(float *p, float v, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    k_fill_f32<<<fill_grid(n), 256, 0, s>>>(p, v, n);
+}
+
+// ---------------------------------------------------------------------------
+// block-wide exclusive scan for 64-lane wavefronts
+// ---------------------------------------------------------------------------
+template <int BS>
+__device__ __forceinline__ int block_exclusive_scan(int v, int &total, int *wsum) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    int x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[wid] = x;
+    __syncthreads();
+    if (wid == 0) {
+        int s = (lane < BS / 64) ? wsum[lane] : 0;
+#pragma unroll
+        for (int o = 1; o < BS / 64; o <<= 1) {
+            int y = __shfl_up(s, o, 64);
+            if (lane >= o) s += y;
+        }
+        if (lane < BS / 64) wsum[lane] = s;
+    }
+    __syncthreads();
+    int base = wid ? wsum[wid - 1] : 0;
+    total = wsum[BS / 64 - 1];
+    __syncthreads();
+    return base + x - v;
+}
+
+#define SCAN_BS 256
+#define SCAN_PER 4
+#define SCAN_CHUNK (SCAN_BS * SCAN_PER)
+
+__global__ void __launch_bounds__(SCAN_BS) k_scan_reduce(const int32_t *in, int64_t n,
+                                                         int32_t *block_sums) {
+    __shared__ int wsum[SCAN_BS / 64];
+    int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK + (int64_t)threadIdx.x * SCAN_PER;
+    int s = 0;
+#pragma unroll
+    for (int j = 0; j < SCAN_PER; j++)
+        if (base + j < n) s += in[base + j];
+    int total;
+    block_exclusive_scan<SCAN_BS>(s, total, wsum);
+    if (threadIdx.x == 0) block_sums[blockIdx.x] = total;
+}
+
+// single block: exclusive scan of the block sums in place
+__global__ void __launch_bounds__(1024) k_scan_blocks(int32_t *sums, int nb) {
+    __shared__ int wsum[16];
+    __shared__ int carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int start = 0; start < nb; start += 1024) {
+        int i = start + threadIdx.x;
+        int v = i < nb ? sums[i] : 0;
+        int total;
+        int ex = block_exclusive_scan<1024>(v, total, wsum);
+        if (i < nb) sums[i] = carry + ex;
+        __syncthreads();
+        if (threadIdx.x == 0) carry += total;
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(SCAN_BS) k_scan_apply(const int32_t *in, int32_t *out, int64_t n,
+                                                        const int32_t *block_offsets) {
+    __shared__ int wsum[SCAN_BS / 64];
+    int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK + (int64_t)threadIdx.x * SCAN_PER;
+    int v[SCAN_PER];
+    int s = 0;
+#pragma unroll
+    for (int j = 0; j < SCAN_PER; j++) {
+        v[j] = (base + j < n) ? in[base + j] : 0;
+        s += v[j];
+    }
+    int total;
+    int ex = block_exclusive_scan<SCAN_BS>(s, total, wsum) + block_offsets[blockIdx.x];
+#pragma unroll
+    for (int j = 0; j < SCAN_PER; j++) {
+        if (base + j < n) out[base + j] = ex;
+        ex += v[j];
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == SCAN_BS - 1) out[n] = ex;
+}
+
+size_t dressi_scan_tmp_bytes(int64_t n) {
+    int64_t nb = (n + SCAN_CHUNK - 1) / SCAN_CHUNK;
+    return (size_t)(nb + 1) * sizeof(int32_t);
+}
+
+void dressi_exclusive_scan(const int32_t *in, int32_t *out, int64_t n, void *tmp, hipStream_t s) {
+    if (n <= 0) {
+        dressi_fill_i32(out, 0, 1, s);
+        return;
+    }
+    int nb = (int)((n + SCAN_CHUNK - 1) / SCAN_CHUNK);
+    int32_t *sums = static_cast<int32_t *>(tmp);
+    k_scan_reduce<<<nb, SCAN_BS, 0, s>>>(in, n, sums);
+    k_scan_blocks<<<1, 1024, 0, s>>>(sums, nb);
+    k_scan_apply<<<nb, SCAN_BS, 0, s>>>(in, out, n, sums);
+}
+
+// ---------------------------------------------------------------------------
+// vertex -> corner adjacency (CSR), each vertex's corners in ascending order
+// ---------------------------------------------------------------------------
+__global__ void k_count_corners(const int32_t *tris, int64_t n3, int V, int32_t *counts) {
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n3) return;
+    int v = tris[c];
+    if (v >= 0 && v < V) atomicAdd(&counts[v], 1);
+}
+
+__global__ void k_place_corners(const int32_t *tris, int64_t n3, int V, const int32_t *offsets,
+                                int32_t *cursor, int32_t *corners) {
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n3) return;
+    int v = tris[c];
+    if (v < 0 || v >= V) return;
+    int slot = offsets[v] + atomicAdd(&cursor[v], 1);
+    corners[slot] = (int32_t)c;
+}
+
+// the atomics above place corners in arbitrary order: sort every list so that
+// gathers sum in a fixed order
+__global__ void k_sort_corners(const int32_t *offsets, int32_t *corners, int V) {
+    int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= V) return;
+    int a = offsets[v], b = offsets[v + 1];
+    for (int i = a + 1; i < b; i++) {
+        int x = corners[i];
+        int j = i - 1;
+        while (j >= a && corners[j] > x) {
+            corners[j + 1] = corners[j];
+            j--;
+        }
+        corners[j + 1] = x;
+    }
+}
+
+size_t dressi_adjacency_bytes(int V, int T) {
+    Carver c;
+    c.take(sizeof(int32_t) * (V + 1));        // offsets
+    c.take(sizeof(int32_t) * 3 * (size_t)T);  // corners
+    c.take(sizeof(int32_t) * V);              // counts
+    c.take(sizeof(int32_t) * V);              // cursor
+    c.take(dressi_scan_tmp_bytes(V));
+    return c.off;
+}
+
+void dressi_build_adjacency(const int32_t *tris, int T, int V, void *scratch, Adjacency &adj,
+                            hipStream_t s) {
+    Carver c;
+    adj.offsets = at<int32_t>(scratch, c.take(sizeof(int32_t) * (V + 1)));
+    adj.corners = at<int32_t>(scratch, c.take(sizeof(int32_t) * 3 * (size_t)T));
+    int32_t *counts = at<int32_t>(scratch, c.take(sizeof(int32_t) * V));
+    int32_t *cursor = at<int32_t>(scratch, c.take(sizeof(int32_t) * V));
+    void *tmp = at<void>(scratch, c.take(dressi_scan_tmp_bytes(V)));
+    int64_t n3 = 3 * (int64_t)T;
+    dressi_fill_i32(counts, 0, V, s);
+    dressi_fill_i32(cursor, 0, V, s);
+    if (n3 > 0) k_count_corners<<<(int)((n3 + 255) / 256), 256, 0, s>>>(tris, n3, V, counts);
+    dressi_exclusive_scan(counts, adj.offsets, V, tmp, s);
+    if (n3 > 0)
+        k_place_corners<<<(int)((n3 + 255) / 256), 256, 0, s>>>(tris, n3, V, adj.offsets, cursor,
+                                                               adj.corners);
+    if (V > 0) k_sort_corners<<<(V + 255) / 256, 256, 0, s>>>(adj.offsets, adj.corners, V);
+}

@@ -1,0 +1,253 @@
+// HardSoftRas blend (§3.4.3, BuildBlend) and its backward for gfx950.
+//
+// Edge mask: the hard stencil S^H of the front layer, its 4-neighbour
+// boundary (both sides), and an L-infinity dilation of radius
+// rho = ceil(delta*W) - 1 done as a row pass then a column pass, integer
+// exact.  The column pass is fused with the per-pixel blend.
+#include "dressi_internal.h"
+
+__device__ __forceinline__ bool front_hard(const int32_t *tri_id, const float *dist, int64_t o) {
+    if (tri_id[o] < 0) return false;
+    if (!dist) return true;
+    return !signbit(dist[o]);
+}
+
+// S^H boundary: pixels whose S^H differs from an in-image 4-neighbour
+__global__ void k_boundary(const int32_t *__restrict__ tri_id, const float *__restrict__ dist,
+                           int B, int K, int H, int W, uint8_t *__restrict__ bnd) {
+    int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t N = (int64_t)H * W;
+    if (gid >= (int64_t)B * N) return;
+    int b = (int)(gid / N);
+    int p = (int)(gid - (int64_t)b * N);
+    int y = p / W, x = p - y * W;
+    int64_t o = (int64_t)b * K * N + p;
+    bool s = front_hard(tri_id, dist, o);
+    bool e = false;
+    if (x > 0) e |= front_hard(tri_id, dist, o - 1) != s;
+    if (x < W - 1) e |= front_hard(tri_id, dist, o + 1) != s;
+    if (y > 0) e |= front_hard(tri_id, dist, o - W) != s;
+    if (y < H - 1) e |= front_hard(tri_id, dist, o + W) != s;
+    bnd[gid] = e ? 1 : 0;
+}
+
+// row pass of the dilation: any boundary pixel within |dx| <= rho
+__global__ void k_dilate_rows(const uint8_t *__restrict__ bnd, int B, int H, int W, int rho,
+                              uint8_t *__restrict__ rows) {
+    int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t N = (int64_t)H * W;
+    if (gid >= (int64_t)B * N) return;
+    int64_t rowbase = gid - (gid % W);
+    int x = (int)(gid % W);
+    int a = max(x - rho, 0), e = min(x + rho, W - 1);
+    uint8_t v = 0;
+    for (int q = a; q <= e && !v; q++) v = bnd[rowbase + q];
+    rows[gid] = v;
+}
+
+__device__ __forceinline__ float sigmoidf_(float x) { return 1.0f / (1.0f + expf(-x)); }
+
+template <int K>
+__global__ void k_blend(const float *__restrict__ color, const float *__restrict__ dist,
+                        const int32_t *__restrict__ tri_id, int B, int H, int W, int Cc,
+                        float inv_sigma, int mode, int rho, const uint8_t *__restrict__ rows,
+                        float *__restrict__ out_color, float *__restrict__ out_sil,
+                        uint8_t *__restrict__ edge) {
+    int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t N = (int64_t)H * W;
+    if (gid >= (int64_t)B * N) return;
+    int b = (int)(gid / N);
+    int p = (int)(gid - (int64_t)b * N);
+    int y = p / W, x = p - y * W;
+    uint8_t E;
+    if (mode == DRESSI_BLEND_SOFTRAS) E = 1;
+    else if (mode == DRESSI_BLEND_HARD || rho < 0) E = 0;
+    else {
+        E = 0;
+        int a = max(y - rho, 0), e = min(y + rho, H - 1);
+        const uint8_t *col = rows + (int64_t)b * N + x;
+        for (int q = a; q <= e && !E; q++) E = col[(int64_t)q * W];
+    }
+    edge[gid] = E;
+    float *oc = out_color + gid * Cc;
+    const int64_t o1 = (int64_t)b * K * N + p;
+    if (!E) {
+        bool sh = front_hard(tri_id, dist, o1);
+        const float *c1 = color + o1 * Cc;
+        for (int c = 0; c < Cc; c++) oc[c] = sh ? c1[c] : 0.0f;
+        out_sil[gid] = sh ? 1.0f : 0.0f;
+        return;
+    }
+    float w[K];
+    float Wsum = 0.0f, prod = 1.0f;
+    int nS = 0;
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+        int64_t o = o1 + (int64_t)k * N;
+        w[k] = 0.0f;
+        if (tri_id[o] < 0) continue;
+        float d = dist ? dist[o] : 0.0f;
+        w[k] = sigmoidf_(d * inv_sigma);
+        nS++;
+        Wsum += w[k];
+        prod *= (1.0f - w[k]);
+    }
+    float inv = nS > 0 ? 1.0f / Wsum : 0.0f;
+    for (int c = 0; c < Cc; c++) {
+        float s = 0.0f;
+#pragma unroll
+        for (int k = 0; k < K; k++)
+            if (w[k] != 0.0f) s += w[k] * color[(o1 + (int64_t)k * N) * Cc + c];
+        oc[c] = s * inv;
+    }
+    out_sil[gid] = 1.0f - prod;
+}
+
+template <int K>
+__global__ void k_blend_bwd(const float *__restrict__ color, const float *__restrict__ dist,
+                            const int32_t *__restrict__ tri_id, int B, int H, int W, int Cc,
+                            float inv_sigma, const uint8_t *__restrict__ edge,
+                            const float *__restrict__ grad_color, const float *__restrict__ grad_sil,
+                            float *__restrict__ grad_layer, float *__restrict__ grad_dist) {
+    int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t N = (int64_t)H * W;
+    if (gid >= (int64_t)B * N) return;
+    int b = (int)(gid / N);
+    int p = (int)(gid - (int64_t)b * N);
+    const int64_t o1 = (int64_t)b * K * N + p;
+    const float *gc = grad_color + gid * Cc;
+    float gs = grad_sil ? grad_sil[gid] : 0.0f;
+    if (!edge[gid]) {
+        bool sh = front_hard(tri_id, dist, o1);
+#pragma unroll
+        for (int k = 0; k < K; k++) {
+            int64_t o = o1 + (int64_t)k * N;
+            float *gl = grad_layer + o * Cc;
+            for (int c = 0; c < Cc; c++) gl[c] = (k == 0 && sh) ? gc[c] : 0.0f;
+            if (grad_dist) grad_dist[o] = 0.0f;
+        }
+        return;
+    }
+    float w[K];
+    bool S[K];
+    float Wsum = 0.0f;
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+        int64_t o = o1 + (int64_t)k * N;
+        S[k] = tri_id[o] >= 0;
+        w[k] = S[k] ? sigmoidf_((dist ? dist[o] : 0.0f) * inv_sigma) : 0.0f;
+        Wsum += w[k];
+    }
+    float inv = Wsum > 0.0f ? 1.0f / Wsum : 0.0f;
+    // g_w_k = g_c . (C_k - I_c) / W + g_s prod_{j != k} (1 - w_j)
+    float gw[K];
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+        float others = 1.0f;
+#pragma unroll
+        for (int j = 0; j < K; j++)
+            if (j != k && S[j]) others *= (1.0f - w[j]);
+        gw[k] = gs * others;
+    }
+    for (int c = 0; c < Cc; c++) {
+        float ic = 0.0f;
+#pragma unroll
+        for (int k = 0; k < K; k++)
+            if (S[k]) ic += w[k] * color[(o1 + (int64_t)k * N) * Cc + c];
+        ic *= inv;
+#pragma unroll
+        for (int k = 0; k < K; k++) {
+            int64_t o = o1 + (int64_t)k * N;
+            if (S[k]) {
+                grad_layer[o * Cc + c] = gc[c] * w[k] * inv;
+                gw[k] += gc[c] * (color[o * Cc + c] - ic) * inv;
+            } else {
+                grad_layer[o * Cc + c] = 0.0f;
+            }
+        }
+    }
+    if (grad_dist) {
+#pragma unroll
+        for (int k = 0; k < K; k++) {
+            int64_t o = o1 + (int64_t)k * N;
+            grad_dist[o] = S[k] ? gw[k] * w[k] * (1.0f - w[k]) * inv_sigma : 0.0f;
+        }
+    }
+}
+
+static int check_softras(dressi_ctx *ctx, const void *color, const void *tid, int B, int K, int H,
+                         int W, int Cc, float sigma, int mode) {
+    if (!ctx) return DRESSI_EINVAL;
+    if (B < 0 || K < 1 || K > DRESSI_MAX_K || H < 0 || W < 0)
+        return dressi_fail(ctx, DRESSI_EINVAL, "softras: bad dimensions");
+    if (Cc < 1 || Cc > 16) return dressi_fail(ctx, DRESSI_EINVAL, "softras: Cc must be 1..16");
+    if (mode < DRESSI_BLEND_HSR || mode > DRESSI_BLEND_HARD)
+        return dressi_fail(ctx, DRESSI_EINVAL, "softras: bad mode");
+    if (mode != DRESSI_BLEND_HARD && !(sigma > 0.0f))
+        return dressi_fail(ctx, DRESSI_EINVAL, "softras: sigma must be > 0");
+    if ((int64_t)B * H * W > 0 && (!color || !tid)) return dressi_fail(ctx, DRESSI_EINVAL, "softras: null input");
+    return DRESSI_OK;
+}
+
+#define KDISPATCH(K, ...)                                  \
+    switch (K) {                                           \
+    case 1: { constexpr int KK = 1; __VA_ARGS__; } break;  \
+    case 2: { constexpr int KK = 2; __VA_ARGS__; } break;  \
+    case 3: { constexpr int KK = 3; __VA_ARGS__; } break;  \
+    case 4: { constexpr int KK = 4; __VA_ARGS__; } break;  \
+    default: { constexpr int KK = 5; __VA_ARGS__; } break; \
+    }
+
+extern "C" int dressi_softras(dressi_ctx *ctx, const float *color, const float *dist,
+                              const int32_t *tri_id, int B, int K, int H, int W, int Cc,
+                              float sigma, float delta, int mode, float *out_color, float *out_sil,
+                              uint8_t *edge_mask, void *stream) {
+    int rc = check_softras(ctx, color, tri_id, B, K, H, W, Cc, sigma, mode);
+    if (rc) return rc;
+    int64_t n = (int64_t)B * H * W;
+    if (n == 0) return DRESSI_OK;
+    if (!out_color || !out_sil || !edge_mask)
+        return dressi_fail(ctx, DRESSI_EINVAL, "softras: null output");
+    hipStream_t st = (hipStream_t)stream;
+    int rho = 0;
+    if (mode == DRESSI_BLEND_HSR) rho = (int)ceilf(delta * (float)W) - 1;
+    uint8_t *rows = nullptr;
+    if ((mode == DRESSI_BLEND_HSR || mode == DRESSI_BLEND_AA) && rho >= 0) {
+        Carver c;
+        size_t o_b = c.take((size_t)n);
+        size_t o_r = c.take((size_t)n);
+        rc = dressi_scratch(ctx, c.off, st);
+        if (rc) return rc;
+        uint8_t *bnd = at<uint8_t>(ctx->scratch, o_b);
+        rows = at<uint8_t>(ctx->scratch, o_r);
+        int g = (int)((n + 255) / 256);
+        k_boundary<<<g, 256, 0, st>>>(tri_id, dist, B, K, H, W, bnd);
+        k_dilate_rows<<<g, 256, 0, st>>>(bnd, B, H, W, rho, rows);
+    }
+    float inv_sigma = mode == DRESSI_BLEND_HARD ? 0.0f : 1.0f / sigma;
+    int g = (int)((n + 255) / 256);
+    KDISPATCH(K, k_blend<KK><<<g, 256, 0, st>>>(color, dist, tri_id, B, H, W, Cc, inv_sigma, mode,
+                                                 rho, rows, out_color, out_sil, edge_mask));
+    return dressi_launch_check(ctx, "softras");
+}
+
+extern "C" int dressi_softras_bwd(dressi_ctx *ctx, const float *color, const float *dist,
+                                  const int32_t *tri_id, int B, int K, int H, int W, int Cc,
+                                  float sigma, const uint8_t *edge_mask, const float *grad_color,
+                                  const float *grad_sil, float *grad_layer_color, float *grad_dist,
+                                  void *stream) {
+    int rc = check_softras(ctx, color, tri_id, B, K, H, W, Cc, sigma > 0.0f ? sigma : 1.0f,
+                           DRESSI_BLEND_HSR);
+    if (rc) return rc;
+    int64_t n = (int64_t)B * H * W;
+    if (n == 0) return DRESSI_OK;
+    if (!edge_mask || !grad_color || !grad_layer_color)
+        return dressi_fail(ctx, DRESSI_EINVAL, "softras_bwd: null edge_mask, grad_color or grad_layer_color");
+    hipStream_t st = (hipStream_t)stream;
+    float inv_sigma = sigma > 0.0f ? 1.0f / sigma : 0.0f;
+    int g = (int)((n + 255) / 256);
+    KDISPATCH(K, k_blend_bwd<KK><<<g, 256, 0, st>>>(color, dist, tri_id, B, H, W, Cc, inv_sigma,
+                                                     edge_mask, grad_color, grad_sil,
+                                                     grad_layer_color, grad_dist));
+    return dressi_launch_check(ctx, "softras_bwd");
+}

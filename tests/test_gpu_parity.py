@@ -1,0 +1,316 @@
+"""GPU (gfx950) parity of every libdressi entry point against the CPU oracle.
+
+Inputs come from the seeded scene generators, or from the oracle's own
+upstream outputs; never from the GPU path.  Bars: triangle ids, coverage and
+edge masks bit-exact; values within 1e-5 absolute (1e-5 * max(1,|ref|) for
+extrapolated barycentrics); gradients within ||g - ref|| <= 1e-4 ||ref|| and
+|g - ref| <= 1e-4 max|ref| element-wise.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from helpers import screen_to_clip, to_clip
+from paper_2204_01386_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2204_01386_amd import binding
+    return binding
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def assert_grad_close(g, ref, tol=1e-4, what=""):
+    g = np.asarray(g, np.float64)
+    ref = np.asarray(ref, np.float64)
+    n = np.linalg.norm(ref)
+    assert n > 0, f"{what}: reference gradient is zero"
+    rel = np.linalg.norm(g - ref) / n
+    ew = np.abs(g - ref).max() / np.abs(ref).max()
+    assert rel <= tol and ew <= tol, f"{what}: rel {rel:.3e}, elementwise {ew:.3e}"
+
+
+def assert_vals_close(v, ref, tol=1e-5, what="", scale_by_ref=False):
+    v = np.asarray(v, np.float64)
+    ref = np.asarray(ref, np.float64)
+    lim = tol * (np.maximum(1.0, np.abs(ref)) if scale_by_ref else 1.0)
+    bad = np.abs(v - ref) > lim
+    assert not bad.any(), f"{what}: {bad.sum()} values off, max {np.abs(v - ref).max():.3e}"
+
+
+# ---------------------------------------------------------------------------
+# scenes
+# ---------------------------------------------------------------------------
+def sphere_scene(subdiv=3, views=1, seed=0):
+    p, tris = scenes.noisy_sphere(subdiv, seed)
+    eyes = scenes.camera_ring(views, seed) if views > 1 else np.array([[0.0, 0.0, 3.0]])
+    return to_clip(p, scenes.view_proj(eyes)), tris
+
+
+def random_tiny(seed, T=7, H=16, W=16):
+    rng = np.random.default_rng(seed)
+    xy = rng.uniform(-2, W + 2, (T * 3, 2))
+    z = rng.uniform(0.05, 0.95, T * 3)
+    w = rng.uniform(0.5, 2.0, T * 3)
+    pc = screen_to_clip(xy, H, W, z=z, w=w)
+    tris = rng.permutation(T * 3).reshape(T, 3).astype(np.int32)
+    tris = np.concatenate([tris, tris[:1], tris[1:2, [1, 0, 2]]]).astype(np.int32)
+    return pc, tris
+
+
+def tiling(H, W, step, fan):
+    xs = np.arange(-step + 0.5, W + step, step)
+    ys = np.arange(-step + 0.5, H + step, step)
+    P = np.stack(np.meshgrid(xs, ys, indexing="xy"), -1)
+    tri = []
+    for i in range(P.shape[0] - 1):
+        for j in range(P.shape[1] - 1):
+            a, b, c, d = P[i, j], P[i, j + 1], P[i + 1, j + 1], P[i + 1, j]
+            if fan:
+                m = (a + c) / 2
+                tri += [(a, b, m), (b, c, m), (c, d, m), (d, a, m)]
+            else:
+                tri += [(a, b, c), (a, c, d)]
+    T = len(tri)
+    xy = np.asarray(tri, np.float64).reshape(-1, 2)
+    z = np.repeat(0.1 + 0.8 * (np.arange(T) + 0.5) / T, 3)
+    return screen_to_clip(xy, H, W, z=z), np.arange(3 * T, dtype=np.int32).reshape(T, 3)
+
+
+def check_raster(B, pc, tris, H, W, K, r, cull=0, seed=0, bwd=True):
+    if pc.ndim == 2:
+        pc = pc[None]
+    tid_o, hard_o, bary_o, dist_o = oracle.rasterize(pc, tris, H, W, K=K, r=r, cull=cull)
+    tid, bary, dist = B.dressi_rasterize(dev(pc), dev(tris), H, W, K, r, cull)
+    tid_g = host(tid)
+    assert np.array_equal(tid_g, tid_o), f"tri_id differs at {np.argwhere(tid_g != tid_o)[:5].tolist()}"
+    assert_vals_close(host(bary), bary_o, what="bary", scale_by_ref=True)
+    if r > 0:
+        d = host(dist)
+        assert_vals_close(d, dist_o, what="dist")
+        m = tid_o >= 0
+        assert np.array_equal(np.signbit(d[m]), hard_o[m] == 0), "hard/soft sign differs"
+    if not bwd:
+        return tid_o
+    rng = np.random.default_rng(seed)
+    gb = rng.standard_normal(bary_o.shape).astype(np.float32)
+    gd = rng.standard_normal(tid_o.shape).astype(np.float32) if r > 0 else None
+    gp = B.dressi_rasterize_bwd(dev(pc), dev(tris), tid, dev(gb), dev(gd) if gd is not None else None,
+                                r, cull)
+    gp_o = oracle.rasterize_bwd(pc, tris, tid_o, hard_o, gb.astype(np.float64),
+                                gd.astype(np.float64) if gd is not None else None, cull=cull)
+    gp_g = host(gp)
+    assert np.all(gp_g[..., 2] == 0)
+    assert_grad_close(gp_g, gp_o, what="grad_pos_clip")
+    return tid_o
+
+
+# ---------------------------------------------------------------------------
+# rasterize
+# ---------------------------------------------------------------------------
+def test_raster_config1_full(B):
+    s = scenes.config1()
+    check_raster(B, to_clip(s.pos, s.mvp), s.tris, 128, 128, 1, 0.0)
+
+
+@pytest.mark.parametrize("fan", [False, True])
+def test_raster_tiling_exactly_once(B, fan):
+    pc, tris = tiling(48, 40, 4, fan)
+    tid = check_raster(B, pc, tris, 48, 40, 2, 0.0, bwd=False)
+    assert (tid[0, 0] >= 0).all() and (tid[0, 1] < 0).all()
+
+
+@pytest.mark.parametrize("seed,K,r", [(0, 1, 0.0), (1, 2, 0.0), (2, 3, 0.12), (3, 2, 0.2), (4, 5, 0.1)])
+def test_raster_tiny_adversarial(B, seed, K, r):
+    pc, tris = random_tiny(seed)
+    check_raster(B, pc, tris, 16, 16, K, r, seed=seed)
+
+
+def test_raster_ragged_multiview_soft(B):
+    pc, tris = sphere_scene(subdiv=3, views=3, seed=2)
+    check_raster(B, pc, tris, 100, 75, 3, 0.04, seed=5)
+
+
+def test_raster_cull_back(B):
+    pc, tris = sphere_scene(subdiv=3)
+    tid_c = check_raster(B, pc, tris, 96, 96, 1, 0.0, cull=1)
+    tid_n, _, _, _ = oracle.rasterize(pc, tris, 96, 96, 1)
+    assert np.array_equal(tid_c, tid_n)
+
+
+def test_raster_config2_full_size(B):
+    s = scenes.config2()
+    check_raster(B, to_clip(s.pos, s.mvp), s.tris, 512, 512, 1, 0.0, seed=7)
+
+
+def test_raster_config3_views_full_size(B):
+    s = scenes.config3()
+    pc = to_clip(s.pos, s.mvp[:2])
+    check_raster(B, pc, s.tris, 512, 512, 3, 0.01, seed=8)
+
+
+def test_raster_empty_inputs(B):
+    pc = np.zeros((1, 3, 4), np.float32)
+    tris = np.zeros((0, 3), np.int32)
+    tid, bary, _ = B.dressi_rasterize(dev(pc), dev(tris), 20, 20, 2, 0.0, 0)
+    assert (host(tid) == -1).all() and (host(bary) == 0).all()
+    gp = B.dressi_rasterize_bwd(dev(pc), dev(tris), tid, torch.zeros_like(bary))
+    assert (host(gp) == 0).all()
+
+
+def test_raster_deterministic(B):
+    pc, tris = sphere_scene(subdiv=4, views=2, seed=3)
+    tid, bary, dist = B.dressi_rasterize(dev(pc), dev(tris), 128, 128, 3, 0.03, 0)
+    g = torch.randn_like(bary)
+    gd = torch.randn_like(dist)
+    a = host(B.dressi_rasterize_bwd(dev(pc), dev(tris), tid, g, gd, 0.03))
+    b_ = host(B.dressi_rasterize_bwd(dev(pc), dev(tris), tid, g, gd, 0.03))
+    assert np.array_equal(a, b_)
+
+
+def test_raster_status_clean(B):
+    ctx = B.context()
+    assert ctx.check_status() == 0
+
+
+# ---------------------------------------------------------------------------
+# interpolate
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("C,Ba", [(6, 1), (11, 1), (20, 2), (3, 2)])
+def test_interpolate(B, C, Ba):
+    pc, tris = sphere_scene(subdiv=3, views=2, seed=1)
+    H, W, K = 72, 90, 2
+    tid_o, hard_o, bary_o, _ = oracle.rasterize(pc, tris, H, W, K=K, r=0.05)
+    rng = np.random.default_rng(C)
+    V = int(tris.max()) + 1
+    attr = rng.standard_normal((Ba, V, C)).astype(np.float32)
+    bary32 = bary_o.astype(np.float32)
+    out_o = oracle.interpolate(attr, tris, tid_o, bary32)
+    out = B.dressi_interpolate(dev(attr), dev(tris), dev(tid_o), dev(bary32))
+    assert_vals_close(host(out), out_o, what="interpolate")
+    g = rng.standard_normal(out_o.shape).astype(np.float32)
+    ga_o, gb_o = oracle.interpolate_bwd(attr, tris, tid_o, bary32, g)
+    ga, gb = B.dressi_interpolate_bwd(dev(attr), dev(tris), dev(tid_o), dev(bary32), dev(g))
+    assert_grad_close(host(ga), ga_o, what="grad_attr")
+    assert_grad_close(host(gb), gb_o, what="grad_bary")
+
+
+def test_interpolate_seam_attr_tris(B):
+    s = scenes.config2(subdiv=3, H=64, tex_size=64)
+    pc = to_clip(s.pos, s.mvp)
+    tid_o, _, bary_o, _ = oracle.rasterize(pc, s.tris, 64, 64, K=1)
+    bary32 = bary_o.astype(np.float32)
+    out_o = oracle.interpolate(s.uv, s.uv_tris, tid_o, bary32)
+    out = B.dressi_interpolate(dev(s.uv), dev(s.uv_tris), dev(tid_o), dev(bary32))
+    assert_vals_close(host(out), out_o, what="uv")
+    g = np.random.default_rng(0).standard_normal(out_o.shape).astype(np.float32)
+    ga_o, _ = oracle.interpolate_bwd(s.uv, s.uv_tris, tid_o, bary32, g)
+    ga, _ = B.dressi_interpolate_bwd(dev(s.uv), dev(s.uv_tris), dev(tid_o), dev(bary32), dev(g))
+    assert_grad_close(host(ga), ga_o, what="grad_uv_attr")
+
+
+# ---------------------------------------------------------------------------
+# texture
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("wrap", [(0, 1), (1, 1), (0, 0)])
+@pytest.mark.parametrize("Ct", [4, 3, 1])
+def test_texture_2d(B, wrap, Ct):
+    rng = np.random.default_rng(Ct * 10 + wrap[0])
+    tex = rng.random((33, 40, Ct)).astype(np.float32)
+    S, H, W = 3, 37, 29
+    uv = rng.uniform(-0.3, 1.3, (S, H, W, 2)).astype(np.float32)
+    tid = rng.integers(-1, 5, (S, H, W)).astype(np.int32)
+    out_o = oracle.texture(tex, uv, tid, wrap_u=wrap[0], wrap_v=wrap[1])
+    out = B.dressi_texture(dev(tex), dev(uv), dev(tid), 0, wrap[0], wrap[1])
+    assert_vals_close(host(out), out_o, what="texture")
+    g = rng.standard_normal(out_o.shape).astype(np.float32)
+    gc_o = oracle.texture_bwd_coord(tex, uv, g, tid, wrap_u=wrap[0], wrap_v=wrap[1])
+    gt_o = oracle.texture_bwd_tex(tex.shape, uv, tid, g, wrap_u=wrap[0], wrap_v=wrap[1])
+    gt, gc = B.dressi_texture_bwd(dev(tex), dev(uv), dev(tid), dev(g), 0, wrap[0], wrap[1])
+    assert_grad_close(host(gc), gc_o, what="grad_uv")
+    assert_grad_close(host(gt), gt_o, what="grad_tex")
+
+
+def test_texture_cube(B):
+    rng = np.random.default_rng(3)
+    cube = rng.random((6, 16, 16, 3)).astype(np.float32)
+    S, H, W = 2, 40, 33
+    d = rng.standard_normal((S, H, W, 3)).astype(np.float32)
+    tid = rng.integers(-1, 5, (S, H, W)).astype(np.int32)
+    out_o = oracle.texture(cube, d, tid, kind=oracle.TEX_CUBE)
+    out = B.dressi_texture(dev(cube), dev(d), dev(tid), 1)
+    assert_vals_close(host(out), out_o, what="cube")
+    g = rng.standard_normal(out_o.shape).astype(np.float32)
+    gc_o = oracle.texture_bwd_coord(cube, d, g, tid, kind=oracle.TEX_CUBE)
+    gt_o = oracle.texture_bwd_tex(cube.shape, d, tid, g, kind=oracle.TEX_CUBE)
+    gt, gc = B.dressi_texture_bwd(dev(cube), dev(d), dev(tid), dev(g), 1)
+    assert_grad_close(host(gc), gc_o, what="grad_dir")
+    assert_grad_close(host(gt), gt_o, what="grad_cube")
+
+
+def test_texture_config2_full(B):
+    """Config-2 sizes: 512^2 UVs from the oracle's raster of the 81,920-triangle
+    mesh on the 1024^2 RGBA texture."""
+    s = scenes.config2()
+    pc = to_clip(s.pos, s.mvp)
+    tid_o, _, bary_o, _ = oracle.rasterize(pc, s.tris, 512, 512, K=1)
+    uv = oracle.interpolate(s.uv, s.uv_tris, tid_o, bary_o.astype(np.float32)).astype(np.float32)
+    uv = uv.reshape(1, 512, 512, 2)
+    t = tid_o.reshape(1, 512, 512)
+    out_o = oracle.texture(s.tex, uv, t)
+    out = B.dressi_texture(dev(s.tex), dev(uv), dev(t))
+    assert_vals_close(host(out), out_o, what="texture cfg2")
+    g = np.random.default_rng(1).standard_normal(out_o.shape).astype(np.float32)
+    gt_o = oracle.texture_bwd_tex(s.tex.shape, uv, t, g)
+    gt, gc = B.dressi_texture_bwd(dev(s.tex), dev(uv), dev(t), dev(g))
+    assert_grad_close(host(gt), gt_o, what="grad_tex cfg2")
+
+
+# ---------------------------------------------------------------------------
+# softras
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("mode", [0, 1, 2, 3])
+def test_softras(B, mode):
+    pc, tris = sphere_scene(subdiv=3, views=2, seed=4)
+    H, W, K, r = 80, 80, 3, 0.06
+    tid_o, hard_o, _, dist_o = oracle.rasterize(pc, tris, H, W, K=K, r=r)
+    rng = np.random.default_rng(mode)
+    col = rng.random(tid_o.shape + (3,)).astype(np.float32)
+    dist32 = dist_o.astype(np.float32)
+    sigma, delta = r / 7, r
+    oc_o, os_o, E_o = oracle.softras(col, dist32, tid_o, sigma, delta, mode)
+    oc, os_, E = B.dressi_softras(dev(col), dev(dist32), dev(tid_o), sigma, delta, mode)
+    assert np.array_equal(host(E), E_o)
+    assert_vals_close(host(oc), oc_o, what="color")
+    assert_vals_close(host(os_), os_o, what="sil")
+    gc = rng.standard_normal(oc_o.shape).astype(np.float32)
+    gs = rng.standard_normal(os_o.shape).astype(np.float32)
+    gl_o, gd_o = oracle.softras_bwd(col, dist32, tid_o, sigma, E_o, gc, gs)
+    gl, gd = B.dressi_softras_bwd(dev(col), dev(dist32), dev(tid_o), sigma, E, dev(gc), dev(gs))
+    assert_grad_close(host(gl), gl_o, what="grad_layer_color")
+    if mode != 3:
+        assert_grad_close(host(gd), gd_o, what="grad_dist")
+
+
+def test_softras_hard_only_no_dist(B):
+    pc, tris = sphere_scene(subdiv=3)
+    tid_o, _, _, _ = oracle.rasterize(pc, tris, 64, 64)
+    col = np.random.default_rng(0).random(tid_o.shape + (3,)).astype(np.float32)
+    oc_o, os_o, _ = oracle.softras(col, None, tid_o, 1.0, 0.0, oracle.BLEND_HARD)
+    oc, os_, E = B.dressi_softras(dev(col), None, dev(tid_o), 1.0, 0.0, 3)
+    assert (host(E) == 0).all()
+    assert_vals_close(host(oc), oc_o)
+    assert_vals_close(host(os_), os_o)
