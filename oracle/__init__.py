@@ -291,3 +291,142 @@ def softras_bwd(color, dist, tri_id, sigma, E, grad_color, grad_sil):
     _check(f(_p(col), _p(dd), _p(tid), B, K, H, W, Cc, sigma, _p(_u8(E)), _p(_f64(grad_color)),
              _p(gs), _p(gl), _p(gd)), "softras_bwd")
     return gl, gd
+
+
+# ---------------------------------------------------------------------------
+# transform, normals, shading, loss
+# ---------------------------------------------------------------------------
+SHADE_LAMBERT, SHADE_PHONG, SHADE_PHONG_ENV = 0, 1, 2
+
+
+def transform(pos, mvp):
+    p = _f64(pos)
+    m = _f64(mvp)
+    if m.ndim == 2:
+        m = m[None]
+    B, V = m.shape[0], p.shape[0]
+    out = np.empty((B, V, 4), np.float64)
+    f = lib().orc_transform
+    f.argtypes = [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_void_p]
+    _check(f(_p(p), _p(m), B, V, _p(out)), "transform")
+    return out
+
+
+def transform_bwd(mvp, grad_clip):
+    m = _f64(mvp)
+    if m.ndim == 2:
+        m = m[None]
+    g = _f64(grad_clip)
+    B, V = g.shape[0], g.shape[1]
+    out = np.empty((V, 3), np.float64)
+    f = lib().orc_transform_bwd
+    f.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p]
+    _check(f(_p(m), B, V, _p(g), _p(out)), "transform_bwd")
+    return out
+
+
+def vertex_normals(pos, tris):
+    p = _f64(pos)
+    t = _i32(tris)
+    out = np.empty_like(p)
+    f = lib().orc_vertex_normals
+    f.argtypes = [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_void_p]
+    _check(f(_p(p), _p(t), p.shape[0], t.shape[0], _p(out)), "vertex_normals")
+    return out
+
+
+def vertex_normals_bwd(pos, tris, grad_n):
+    p = _f64(pos)
+    t = _i32(tris)
+    out = np.empty_like(p)
+    f = lib().orc_vertex_normals_bwd
+    f.argtypes = [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p]
+    _check(f(_p(p), _p(t), p.shape[0], t.shape[0], _p(_f64(grad_n)), _p(out)), "vertex_normals_bwd")
+    return out
+
+
+def normal_map(n, t, m, tri_id):
+    n_, t_, m_ = _f64(n), _f64(t), _f64(m)
+    out = np.empty_like(n_)
+    f = lib().orc_normal_map
+    f.argtypes = [C.c_void_p] * 4 + [C.c_int64, C.c_void_p]
+    _check(f(_p(n_), _p(t_), _p(m_), _p(_i32(tri_id)), n_.size // 3, _p(out)), "normal_map")
+    return out
+
+
+def normal_map_bwd(n, t, m, tri_id, g):
+    n_, t_, m_ = _f64(n), _f64(t), _f64(m)
+    gn, gt, gm = np.empty_like(n_), np.empty_like(n_), np.empty_like(n_)
+    f = lib().orc_normal_map_bwd
+    f.argtypes = [C.c_void_p] * 4 + [C.c_int64] + [C.c_void_p] * 4
+    _check(f(_p(n_), _p(t_), _p(m_), _p(_i32(tri_id)), n_.size // 3, _p(_f64(g)), _p(gn), _p(gt),
+             _p(gm)), "normal_map_bwd")
+    return gn, gt, gm
+
+
+def reflect(n, pos, eye, tri_id):
+    n_, p_ = _f64(n), _f64(pos)
+    tid = _i32(tri_id)
+    B = tid.shape[0]
+    out = np.empty_like(n_)
+    f = lib().orc_reflect
+    f.argtypes = [C.c_void_p] * 4 + [C.c_int, C.c_int64, C.c_void_p]
+    _check(f(_p(n_), _p(p_), _p(_f64(eye)), _p(tid), B, tid.size // B, _p(out)), "reflect")
+    return out
+
+
+def reflect_bwd(n, pos, eye, tri_id, g):
+    n_, p_ = _f64(n), _f64(pos)
+    tid = _i32(tri_id)
+    B = tid.shape[0]
+    gn, gp = np.empty_like(n_), np.empty_like(n_)
+    f = lib().orc_reflect_bwd
+    f.argtypes = [C.c_void_p] * 4 + [C.c_int, C.c_int64] + [C.c_void_p] * 3
+    _check(f(_p(n_), _p(p_), _p(_f64(eye)), _p(tid), B, tid.size // B, _p(_f64(g)), _p(gn), _p(gp)),
+           "reflect_bwd")
+    return gn, gp
+
+
+def shade(mode, n, pos, albedo, env, eye, tri_id):
+    n_ = _f64(n)
+    a = _f64(albedo)
+    Ca = a.shape[-1]
+    tid = _i32(tri_id)
+    B = tid.shape[0]
+    out = np.empty(tid.shape + (3,), np.float64)
+    f = lib().orc_shade
+    f.argtypes = [C.c_int] + [C.c_void_p] * 3 + [C.c_int] + [C.c_void_p] * 3 + [C.c_int, C.c_int64,
+                                                                                 C.c_void_p]
+    _check(f(mode, _p(n_), _p(_f64(pos) if pos is not None else None), _p(a), Ca,
+             _p(_f64(env) if env is not None else None), _p(_f64(eye)), _p(tid), B, tid.size // B,
+             _p(out)), "shade")
+    return out
+
+
+def shade_bwd(mode, n, pos, albedo, env, eye, tri_id, g):
+    n_ = _f64(n)
+    a = _f64(albedo)
+    Ca = a.shape[-1]
+    tid = _i32(tri_id)
+    B = tid.shape[0]
+    gn = np.empty_like(n_)
+    gp = np.empty_like(n_) if pos is not None else None
+    ga = np.empty_like(a)
+    ge = np.empty_like(n_) if env is not None else None
+    f = lib().orc_shade_bwd
+    f.argtypes = [C.c_int] + [C.c_void_p] * 3 + [C.c_int] + [C.c_void_p] * 3 + [C.c_int, C.c_int64] \
+        + [C.c_void_p] * 5
+    _check(f(mode, _p(n_), _p(_f64(pos) if pos is not None else None), _p(a), Ca,
+             _p(_f64(env) if env is not None else None), _p(_f64(eye)), _p(tid), B, tid.size // B,
+             _p(_f64(g)), _p(gn), _p(gp), _p(ga), _p(ge)), "shade_bwd")
+    return gn, gp, ga, ge
+
+
+def loss_l2(color, sil, target):
+    c, s, t = _f64(color), _f64(sil), _f64(target)
+    gc, gs = np.empty_like(c), np.empty_like(s)
+    L = C.c_double(0.0)
+    f = lib().orc_loss_l2
+    f.argtypes = [C.c_void_p] * 3 + [C.c_int64] + [C.c_void_p] * 3
+    _check(f(_p(c), _p(s), _p(t), s.size, C.byref(L), _p(gc), _p(gs)), "loss_l2")
+    return L.value, gc, gs

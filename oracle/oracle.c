@@ -1017,3 +1017,368 @@ int orc_softras_bwd(const double *color, const double *dist, const int32_t *tri_
         }
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Vertex transform, vertex normals, shading and loss (§3.4.1 decomposition */
+/* I = f_pp(f_shade(f_rasterize(...))); the listing's BuildRasterize and    */
+/* BuildNormalCompute; deferred shading per layer, §3.4.3)                  */
+/* ------------------------------------------------------------------------ */
+
+/* pos_clip[b,v] = M_b [p_v, 1] (column vector), M_b = projection x view. */
+int orc_transform(const double *pos, const double *mvp, int B, int V, double *out)
+{
+    for (int b = 0; b < B; b++) {
+        const double *M = mvp + 16 * (int64_t)b;
+        for (int v = 0; v < V; v++) {
+            const double *p = pos + 3 * (int64_t)v;
+            double *o = out + 4 * ((int64_t)b * V + v);
+            for (int r = 0; r < 4; r++)
+                o[r] = M[4 * r] * p[0] + M[4 * r + 1] * p[1] + M[4 * r + 2] * p[2] + M[4 * r + 3];
+        }
+    }
+    return 0;
+}
+
+int orc_transform_bwd(const double *mvp, int B, int V, const double *grad_clip, double *grad_pos)
+{
+    memset(grad_pos, 0, sizeof(double) * 3 * (size_t)V);
+    for (int b = 0; b < B; b++) {
+        const double *M = mvp + 16 * (int64_t)b;
+        for (int v = 0; v < V; v++) {
+            const double *g = grad_clip + 4 * ((int64_t)b * V + v);
+            for (int c = 0; c < 3; c++)
+                grad_pos[3 * (int64_t)v + c] += M[c] * g[0] + M[4 + c] * g[1] + M[8 + c] * g[2] + M[12 + c] * g[3];
+        }
+    }
+    return 0;
+}
+
+static void cross3(const double *a, const double *b, double *o)
+{
+    o[0] = a[1] * b[2] - a[2] * b[1];
+    o[1] = a[2] * b[0] - a[0] * b[2];
+    o[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+/* Vertex normal = normalize(sum over incident faces of (p1-p0) x (p2-p0)),
+ * i.e. face normals weighted by twice their area. */
+int orc_vertex_normals(const double *pos, const int32_t *tris, int V, int T, double *out)
+{
+    double *acc = (double *)calloc((size_t)V * 3, sizeof(double));
+    if (!acc) return -2;
+    for (int t = 0; t < T; t++) {
+        const int32_t *f = tris + 3 * (int64_t)t;
+        double e1[3], e2[3], n[3];
+        for (int c = 0; c < 3; c++) {
+            e1[c] = pos[3 * f[1] + c] - pos[3 * f[0] + c];
+            e2[c] = pos[3 * f[2] + c] - pos[3 * f[0] + c];
+        }
+        cross3(e1, e2, n);
+        for (int i = 0; i < 3; i++)
+            for (int c = 0; c < 3; c++) acc[3 * f[i] + c] += n[c];
+    }
+    for (int v = 0; v < V; v++) {
+        double *a = acc + 3 * v;
+        double l = sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+        for (int c = 0; c < 3; c++) out[3 * v + c] = l > 0 ? a[c] / l : 0.0;
+    }
+    free(acc);
+    return 0;
+}
+
+/* gradient of normalize(a): (g - (g.n) n) / |a| */
+static void normalize_bwd(const double *a, const double *g, double *ga)
+{
+    double l = sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+    if (!(l > 0)) { ga[0] = ga[1] = ga[2] = 0.0; return; }
+    double n[3] = {a[0] / l, a[1] / l, a[2] / l};
+    double d = g[0] * n[0] + g[1] * n[1] + g[2] * n[2];
+    for (int c = 0; c < 3; c++) ga[c] = (g[c] - d * n[c]) / l;
+}
+
+int orc_vertex_normals_bwd(const double *pos, const int32_t *tris, int V, int T,
+                           const double *grad_n, double *grad_pos)
+{
+    double *acc = (double *)calloc((size_t)V * 3, sizeof(double));
+    double *gacc = (double *)calloc((size_t)V * 3, sizeof(double));
+    if (!acc || !gacc) { free(acc); free(gacc); return -2; }
+    for (int t = 0; t < T; t++) {
+        const int32_t *f = tris + 3 * (int64_t)t;
+        double e1[3], e2[3], n[3];
+        for (int c = 0; c < 3; c++) {
+            e1[c] = pos[3 * f[1] + c] - pos[3 * f[0] + c];
+            e2[c] = pos[3 * f[2] + c] - pos[3 * f[0] + c];
+        }
+        cross3(e1, e2, n);
+        for (int i = 0; i < 3; i++)
+            for (int c = 0; c < 3; c++) acc[3 * f[i] + c] += n[c];
+    }
+    for (int v = 0; v < V; v++) normalize_bwd(acc + 3 * v, grad_n + 3 * v, gacc + 3 * v);
+    memset(grad_pos, 0, sizeof(double) * 3 * (size_t)V);
+    for (int t = 0; t < T; t++) {
+        const int32_t *f = tris + 3 * (int64_t)t;
+        double gn[3] = {0, 0, 0}, e1[3], e2[3], g1[3], g2[3];
+        for (int i = 0; i < 3; i++)
+            for (int c = 0; c < 3; c++) gn[c] += gacc[3 * f[i] + c];
+        for (int c = 0; c < 3; c++) {
+            e1[c] = pos[3 * f[1] + c] - pos[3 * f[0] + c];
+            e2[c] = pos[3 * f[2] + c] - pos[3 * f[0] + c];
+        }
+        /* n = e1 x e2: dn.gn = gn.(de1 x e2) + gn.(e1 x de2) -> ge1 = e2 x gn, ge2 = gn x e1 */
+        cross3(e2, gn, g1);
+        cross3(gn, e1, g2);
+        for (int c = 0; c < 3; c++) {
+            grad_pos[3 * f[1] + c] += g1[c];
+            grad_pos[3 * f[2] + c] += g2[c];
+            grad_pos[3 * f[0] + c] -= g1[c] + g2[c];
+        }
+    }
+    free(acc);
+    free(gacc);
+    return 0;
+}
+
+/* Tangent-space normal mapping: n^ = normalize(n), t^ = normalize(t - (t.n^) n^),
+ * b^ = n^ x t^, out = normalize(m_x t^ + m_y b^ + m_z n^). */
+static void nmap_fwd(const double *n, const double *t, const double *m, double *out,
+                     double *nh, double *tp, double *th, double *bh, double *u)
+{
+    double ln = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+    for (int c = 0; c < 3; c++) nh[c] = n[c] / ln;
+    double d = t[0] * nh[0] + t[1] * nh[1] + t[2] * nh[2];
+    for (int c = 0; c < 3; c++) tp[c] = t[c] - d * nh[c];
+    double lt = sqrt(tp[0] * tp[0] + tp[1] * tp[1] + tp[2] * tp[2]);
+    for (int c = 0; c < 3; c++) th[c] = tp[c] / lt;
+    cross3(nh, th, bh);
+    for (int c = 0; c < 3; c++) u[c] = m[0] * th[c] + m[1] * bh[c] + m[2] * nh[c];
+    double lu = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    for (int c = 0; c < 3; c++) out[c] = u[c] / lu;
+}
+
+int orc_normal_map(const double *n, const double *t, const double *m, const int32_t *tri_id,
+                   int64_t N, double *out)
+{
+    for (int64_t i = 0; i < N; i++) {
+        double nh[3], tp[3], th[3], bh[3], u[3];
+        if (tri_id[i] < 0) { out[3 * i] = out[3 * i + 1] = out[3 * i + 2] = 0.0; continue; }
+        nmap_fwd(n + 3 * i, t + 3 * i, m + 3 * i, out + 3 * i, nh, tp, th, bh, u);
+    }
+    return 0;
+}
+
+int orc_normal_map_bwd(const double *n, const double *t, const double *m, const int32_t *tri_id,
+                       int64_t N, const double *g, double *gn, double *gt, double *gm)
+{
+    for (int64_t i = 0; i < N; i++) {
+        const double *ni = n + 3 * i, *ti = t + 3 * i, *mi = m + 3 * i;
+        double *gni = gn + 3 * i, *gti = gt + 3 * i, *gmi = gm + 3 * i;
+        for (int c = 0; c < 3; c++) gni[c] = gti[c] = gmi[c] = 0.0;
+        if (tri_id[i] < 0) continue;
+        double nh[3], tp[3], th[3], bh[3], u[3], o[3];
+        nmap_fwd(ni, ti, mi, o, nh, tp, th, bh, u);
+        double gu[3];
+        normalize_bwd(u, g + 3 * i, gu);
+        gmi[0] = gu[0] * th[0] + gu[1] * th[1] + gu[2] * th[2];
+        gmi[1] = gu[0] * bh[0] + gu[1] * bh[1] + gu[2] * bh[2];
+        gmi[2] = gu[0] * nh[0] + gu[1] * nh[1] + gu[2] * nh[2];
+        double gth[3], gbh[3], gnh[3];
+        for (int c = 0; c < 3; c++) {
+            gth[c] = mi[0] * gu[c];
+            gbh[c] = mi[1] * gu[c];
+            gnh[c] = mi[2] * gu[c];
+        }
+        /* b = nh x th: gnh += th x gbh, gth += gbh x nh */
+        double tmp[3];
+        cross3(th, gbh, tmp);
+        for (int c = 0; c < 3; c++) gnh[c] += tmp[c];
+        cross3(gbh, nh, tmp);
+        for (int c = 0; c < 3; c++) gth[c] += tmp[c];
+        double gtp[3];
+        normalize_bwd(tp, gth, gtp);
+        /* tp = t - (t.nh) nh */
+        double d = ti[0] * nh[0] + ti[1] * nh[1] + ti[2] * nh[2];
+        double gd = -(gtp[0] * nh[0] + gtp[1] * nh[1] + gtp[2] * nh[2]);
+        for (int c = 0; c < 3; c++) {
+            gti[c] = gtp[c] + gd * nh[c];
+            gnh[c] += -d * gtp[c] + gd * ti[c];
+        }
+        normalize_bwd(ni, gnh, gni);
+    }
+    return 0;
+}
+
+static const double LIGHT[3] = {0.40824829046386302, 0.40824829046386302, 0.81649658092772603};
+
+/* Reflection direction of the view ray for the environment lookup:
+ * d = reflect(-v^, n^) = 2 (n^.v^) n^ - v^, v^ = normalize(eye_b - pos). */
+int orc_reflect(const double *n, const double *pos, const double *eye, const int32_t *tri_id,
+                int B, int64_t Npv, double *out)
+{
+    for (int b = 0; b < B; b++)
+        for (int64_t j = 0; j < Npv; j++) {
+            int64_t i = (int64_t)b * Npv + j;
+            double *o = out + 3 * i;
+            if (tri_id[i] < 0) { o[0] = o[1] = o[2] = 0.0; continue; }
+            double nh[3], vv[3], vh[3];
+            double ln = sqrt(n[3 * i] * n[3 * i] + n[3 * i + 1] * n[3 * i + 1] + n[3 * i + 2] * n[3 * i + 2]);
+            for (int c = 0; c < 3; c++) { nh[c] = n[3 * i + c] / ln; vv[c] = eye[3 * b + c] - pos[3 * i + c]; }
+            double lv = sqrt(vv[0] * vv[0] + vv[1] * vv[1] + vv[2] * vv[2]);
+            for (int c = 0; c < 3; c++) vh[c] = vv[c] / lv;
+            double d = nh[0] * vh[0] + nh[1] * vh[1] + nh[2] * vh[2];
+            for (int c = 0; c < 3; c++) o[c] = 2.0 * d * nh[c] - vh[c];
+        }
+    return 0;
+}
+
+int orc_reflect_bwd(const double *n, const double *pos, const double *eye, const int32_t *tri_id,
+                    int B, int64_t Npv, const double *g, double *gn, double *gpos)
+{
+    for (int b = 0; b < B; b++)
+        for (int64_t j = 0; j < Npv; j++) {
+            int64_t i = (int64_t)b * Npv + j;
+            double *gni = gn + 3 * i, *gpi = gpos + 3 * i;
+            for (int c = 0; c < 3; c++) gni[c] = gpi[c] = 0.0;
+            if (tri_id[i] < 0) continue;
+            double nh[3], vv[3], vh[3];
+            double ln = sqrt(n[3 * i] * n[3 * i] + n[3 * i + 1] * n[3 * i + 1] + n[3 * i + 2] * n[3 * i + 2]);
+            for (int c = 0; c < 3; c++) { nh[c] = n[3 * i + c] / ln; vv[c] = eye[3 * b + c] - pos[3 * i + c]; }
+            double lv = sqrt(vv[0] * vv[0] + vv[1] * vv[1] + vv[2] * vv[2]);
+            for (int c = 0; c < 3; c++) vh[c] = vv[c] / lv;
+            double d = nh[0] * vh[0] + nh[1] * vh[1] + nh[2] * vh[2];
+            const double *go = g + 3 * i;
+            double gdn = go[0] * nh[0] + go[1] * nh[1] + go[2] * nh[2];
+            double gnh[3], gvh[3];
+            for (int c = 0; c < 3; c++) {
+                gnh[c] = 2.0 * d * go[c] + 2.0 * gdn * vh[c];
+                gvh[c] = 2.0 * gdn * nh[c] - go[c];
+            }
+            double gvv[3];
+            normalize_bwd(n + 3 * i, gnh, gni);
+            normalize_bwd(vv, gvh, gvv);
+            for (int c = 0; c < 3; c++) gpi[c] = -gvv[c];
+        }
+    return 0;
+}
+
+/* Deferred shading of one fragment, white directional light l = (1,1,2)/|.|:
+ *   Lambert: c = a_rgb (0.1 + 0.9 max(0, n^.l))
+ *   Phong:   c = a_rgb (0.1 + 0.8 max(0, n^.l)) + 0.2 a_a max(0, r.v^)^32,
+ *            r = 2 (n^.l) n^ - l, v^ = normalize(eye_b - pos)
+ *   + env:   c += 0.5 a_a e  (e = environment sample in the reflection direction)
+ * The derivative of max(0, x) at 0 is taken as 0. */
+static void shade_one(int mode, const double *n, const double *p, const double *a, int Ca,
+                      const double *e, const double *eye, double *c, double *grad_n,
+                      double *grad_p, double *grad_a, double *grad_e, const double *g)
+{
+    double ln = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+    double nh[3] = {n[0] / ln, n[1] / ln, n[2] / ln};
+    double ndl = nh[0] * LIGHT[0] + nh[1] * LIGHT[1] + nh[2] * LIGHT[2];
+    double dif = ndl > 0 ? ndl : 0.0;
+    double kd = mode == ORC_SHADE_LAMBERT ? 0.9 : 0.8;
+    double base = 0.1 + kd * dif;
+    double alpha = Ca > 3 ? a[3] : 0.0;
+    double spec = 0.0, rv = 0.0, vv[3] = {0, 0, 0}, vh[3] = {0, 0, 0}, r[3] = {0, 0, 0}, lv = 1.0;
+    if (mode != ORC_SHADE_LAMBERT) {
+        for (int k = 0; k < 3; k++) vv[k] = eye[k] - p[k];
+        lv = sqrt(vv[0] * vv[0] + vv[1] * vv[1] + vv[2] * vv[2]);
+        for (int k = 0; k < 3; k++) { vh[k] = vv[k] / lv; r[k] = 2.0 * ndl * nh[k] - LIGHT[k]; }
+        rv = r[0] * vh[0] + r[1] * vh[1] + r[2] * vh[2];
+        spec = rv > 0 ? pow(rv, 32.0) : 0.0;
+    }
+    if (c) {
+        for (int k = 0; k < 3; k++) {
+            c[k] = a[k] * base;
+            if (mode != ORC_SHADE_LAMBERT) c[k] += 0.2 * alpha * spec;
+            if (mode == ORC_SHADE_PHONG_ENV) c[k] += 0.5 * alpha * e[k];
+        }
+    }
+    if (!g) return;
+    double gsum = g[0] + g[1] + g[2];
+    double ga_dot = g[0] * a[0] + g[1] * a[1] + g[2] * a[2];
+    for (int k = 0; k < 3; k++) grad_a[k] = g[k] * base;
+    if (Ca > 3) {
+        grad_a[3] = 0.0;
+        if (mode != ORC_SHADE_LAMBERT) grad_a[3] += 0.2 * spec * gsum;
+        if (mode == ORC_SHADE_PHONG_ENV) grad_a[3] += 0.5 * (g[0] * e[0] + g[1] * e[1] + g[2] * e[2]);
+    }
+    if (grad_e) for (int k = 0; k < 3; k++) grad_e[k] = mode == ORC_SHADE_PHONG_ENV ? 0.5 * alpha * g[k] : 0.0;
+    /* d/d ndl of the diffuse term */
+    double g_ndl = ndl > 0 ? kd * ga_dot : 0.0;
+    double gnh[3] = {g_ndl * LIGHT[0], g_ndl * LIGHT[1], g_ndl * LIGHT[2]};
+    double gvh[3] = {0, 0, 0};
+    if (mode != ORC_SHADE_LAMBERT && rv > 0) {
+        double g_rv = 0.2 * alpha * gsum * 32.0 * pow(rv, 31.0);
+        /* rv = r.vh, r = 2 ndl nh - l */
+        double g_r[3], r_dot_dummy;
+        (void)r_dot_dummy;
+        for (int k = 0; k < 3; k++) { g_r[k] = g_rv * vh[k]; gvh[k] = g_rv * r[k]; }
+        double g_ndl2 = 2.0 * (g_r[0] * nh[0] + g_r[1] * nh[1] + g_r[2] * nh[2]);
+        for (int k = 0; k < 3; k++) gnh[k] += 2.0 * ndl * g_r[k] + g_ndl2 * LIGHT[k];
+    }
+    normalize_bwd(n, gnh, grad_n);
+    if (grad_p) {
+        double gvv[3];
+        if (mode != ORC_SHADE_LAMBERT) normalize_bwd(vv, gvh, gvv);
+        else gvv[0] = gvv[1] = gvv[2] = 0.0;
+        for (int k = 0; k < 3; k++) grad_p[k] = -gvv[k];
+    }
+}
+
+int orc_shade(int mode, const double *n, const double *pos, const double *albedo, int Ca,
+              const double *env, const double *eye, const int32_t *tri_id, int B, int64_t Npv,
+              double *out)
+{
+    for (int b = 0; b < B; b++)
+        for (int64_t j = 0; j < Npv; j++) {
+            int64_t i = (int64_t)b * Npv + j;
+            double *o = out + 3 * i;
+            if (tri_id[i] < 0) { o[0] = o[1] = o[2] = 0.0; continue; }
+            shade_one(mode, n + 3 * i, pos ? pos + 3 * i : NULL, albedo + (int64_t)Ca * i, Ca,
+                      env ? env + 3 * i : NULL, eye + 3 * b, o, NULL, NULL, NULL, NULL, NULL);
+        }
+    return 0;
+}
+
+int orc_shade_bwd(int mode, const double *n, const double *pos, const double *albedo, int Ca,
+                  const double *env, const double *eye, const int32_t *tri_id, int B, int64_t Npv,
+                  const double *g, double *gn, double *gpos, double *galb, double *genv)
+{
+    for (int b = 0; b < B; b++)
+        for (int64_t j = 0; j < Npv; j++) {
+            int64_t i = (int64_t)b * Npv + j;
+            double dn[3], dp[3], da[4], de[3];
+            if (tri_id[i] < 0) {
+                memset(dn, 0, sizeof dn); memset(dp, 0, sizeof dp);
+                memset(da, 0, sizeof da); memset(de, 0, sizeof de);
+            } else {
+                shade_one(mode, n + 3 * i, pos ? pos + 3 * i : NULL, albedo + (int64_t)Ca * i, Ca,
+                          env ? env + 3 * i : NULL, eye + 3 * b, NULL, dn, dp, da, de, g + 3 * i);
+            }
+            for (int k = 0; k < 3; k++) {
+                gn[3 * i + k] = dn[k];
+                if (gpos) gpos[3 * i + k] = dp[k];
+                if (genv) genv[3 * i + k] = de[k];
+            }
+            for (int k = 0; k < Ca; k++) galb[(int64_t)Ca * i + k] = da[k];
+        }
+    return 0;
+}
+
+/* L = mean over B*H*W*4 of (RGBA - target)^2 with RGBA = (colour, silhouette). */
+int orc_loss_l2(const double *color, const double *sil, const double *target, int64_t Npix,
+                double *loss, double *grad_color, double *grad_sil)
+{
+    double s = 0.0, inv = 1.0 / (4.0 * (double)Npix);
+    for (int64_t i = 0; i < Npix; i++) {
+        for (int c = 0; c < 3; c++) {
+            double d = color[3 * i + c] - target[4 * i + c];
+            s += d * d;
+            if (grad_color) grad_color[3 * i + c] = 2.0 * d * inv;
+        }
+        double d = sil[i] - target[4 * i + 3];
+        s += d * d;
+        if (grad_sil) grad_sil[i] = 2.0 * d * inv;
+    }
+    *loss = s * inv;
+    return 0;
+}

@@ -61,4 +61,28 @@ int orc_softras_bwd(const double *color, const double *dist, const int32_t *tri_
                     int B, int K, int H, int W, int Cc, double sigma, const uint8_t *E,
                     const double *grad_color, const double *grad_sil,
                     double *grad_layer_color, double *grad_dist);
+#define ORC_SHADE_LAMBERT 0
+#define ORC_SHADE_PHONG 1
+#define ORC_SHADE_PHONG_ENV 2
+int orc_transform(const double *pos, const double *mvp, int B, int V, double *out);
+int orc_transform_bwd(const double *mvp, int B, int V, const double *grad_clip, double *grad_pos);
+int orc_vertex_normals(const double *pos, const int32_t *tris, int V, int T, double *out);
+int orc_vertex_normals_bwd(const double *pos, const int32_t *tris, int V, int T,
+                           const double *grad_n, double *grad_pos);
+int orc_normal_map(const double *n, const double *t, const double *m, const int32_t *tri_id,
+                   int64_t N, double *out);
+int orc_normal_map_bwd(const double *n, const double *t, const double *m, const int32_t *tri_id,
+                       int64_t N, const double *g, double *gn, double *gt, double *gm);
+int orc_reflect(const double *n, const double *pos, const double *eye, const int32_t *tri_id,
+                int B, int64_t Npv, double *out);
+int orc_reflect_bwd(const double *n, const double *pos, const double *eye, const int32_t *tri_id,
+                    int B, int64_t Npv, const double *g, double *gn, double *gpos);
+int orc_shade(int mode, const double *n, const double *pos, const double *albedo, int Ca,
+              const double *env, const double *eye, const int32_t *tri_id, int B, int64_t Npv,
+              double *out);
+int orc_shade_bwd(int mode, const double *n, const double *pos, const double *albedo, int Ca,
+                  const double *env, const double *eye, const int32_t *tri_id, int B, int64_t Npv,
+                  const double *g, double *gn, double *gpos, double *galb, double *genv);
+int orc_loss_l2(const double *color, const double *sil, const double *target, int64_t Npix,
+                double *loss, double *grad_color, double *grad_sil);
 #endif

@@ -177,14 +177,17 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX)
         int64_t E[3];
 #pragma unroll
         for (int i = 0; i < 3; i++) E[i] = dr_edge(s.X, s.Y, i, px, py);
-        float q0 = ((float)E[0] / s.Af) / s.w[0];
-        float q1 = ((float)E[1] / s.Af) / s.w[1];
-        float q2 = ((float)E[2] / s.Af) / s.w[2];
-        float Q = q0 + q1 + q2;
-        float b0 = q0 / Q, b1 = q1 / Q, b2 = q2 / Q;
+        // perspective division in double: soft fragments extrapolate and the
+        // sum of l_i/w_i can come close to zero for grazing triangles
+        const double A2 = (double)s.Af;
+        double q0 = ((double)E[0] / A2) / (double)s.w[0];
+        double q1 = ((double)E[1] / A2) / (double)s.w[1];
+        double q2 = ((double)E[2] / A2) / (double)s.w[2];
+        double Q = q0 + q1 + q2;
+        double b0 = q0 / Q, b1 = q1 / Q, b2 = q2 / Q;
         bool swapped = dr_corner(s.meta, 1) == 2;
         tri_id[o] = t;
-        bary[o] = make_float2(b0, swapped ? b2 : b1);
+        bary[o] = make_float2((float)b0, (float)(swapped ? b2 : b1));
         if (SOFT) {
             int ne;
             float dn = dr_distnorm(s.X, s.Y, px, py, E, dscale, ne);
@@ -542,19 +545,20 @@ __global__ void k_rast_bwd_tri(const float4 *__restrict__ pos_clip, const int32_
         sx[i] = (float)s.X[i] * (1.0f / 256.0f);
         sy[i] = (float)s.Y[i] * (1.0f / 256.0f);
     }
-    const float A = s.Af * (1.0f / 65536.0f);
+    const double A2d = (double)s.Af;
+    const double A = A2d * (1.0 / 65536.0);
     // grad_p lambda_i (pixel units), edge i from a = i+1 to c = i+2
-    float glx[3], gly[3];
+    double glx[3], gly[3];
 #pragma unroll
     for (int i = 0; i < 3; i++) {
         int a = (i + 1) % 3, c = (i + 2) % 3;
-        glx[i] = -(sy[c] - sy[a]) / A;
-        gly[i] = (sx[c] - sx[a]) / A;
+        glx[i] = -((double)s.Y[c] - (double)s.Y[a]) * (1.0 / 256.0) / A;
+        gly[i] = ((double)s.X[c] - (double)s.X[a]) * (1.0 / 256.0) / A;
     }
     const bool swapped = dr_corner(s.meta, 1) == 2;
     const float dscale = (float)W * 256.0f;
     const float invW = 1.0f / (float)W;
-    float gsx[3] = {0, 0, 0}, gsy[3] = {0, 0, 0}, gw[3] = {0, 0, 0};
+    double gsx[3] = {0, 0, 0}, gsy[3] = {0, 0, 0}, gw[3] = {0, 0, 0};
     int tx0 = (s.box0 & 0xffff) / DRESSI_TILE, tx1 = (s.box0 >> 16) / DRESSI_TILE;
     int ty0 = (s.box1 & 0xffff) / DRESSI_TILE, ty1 = (s.box1 >> 16) / DRESSI_TILE;
     for (int ty = ty0; ty <= ty1; ty++)
@@ -577,23 +581,25 @@ __global__ void k_rast_bwd_tri(const float4 *__restrict__ pos_clip, const int32_
                     bool own = (s.meta >> (1 + i)) & 1;
                     in = in && (E[i] > 0 || (E[i] == 0 && own));
                 }
-                float l[3], q[3];
+                // the barycentric chain runs in double (see the forward)
+                double l[3], q[3];
 #pragma unroll
                 for (int i = 0; i < 3; i++) {
-                    l[i] = (float)E[i] / s.Af;
-                    q[i] = l[i] / s.w[i];
+                    l[i] = (double)E[i] / A2d;
+                    q[i] = l[i] / (double)s.w[i];
                 }
-                float Q = q[0] + q[1] + q[2];
+                double Q = q[0] + q[1] + q[2];
                 float2 g2 = grad_bary[o];
                 // gradient on the normalised-order barycentrics (original corner 2 has none)
-                float gb[3] = {g2.x, swapped ? 0.0f : g2.y, swapped ? g2.y : 0.0f};
-                float sb = (gb[0] * q[0] + gb[1] * q[1] + gb[2] * q[2]) / Q;
-                float Gx = 0.0f, Gy = 0.0f;
+                double gb[3] = {g2.x, swapped ? 0.0 : (double)g2.y, swapped ? (double)g2.y : 0.0};
+                double sb = (gb[0] * q[0] + gb[1] * q[1] + gb[2] * q[2]) / Q;
+                double Gx = 0.0, Gy = 0.0;
 #pragma unroll
                 for (int i = 0; i < 3; i++) {
-                    float gq = (gb[i] - sb) / Q;
-                    float gl = gq / s.w[i];
-                    gw[i] -= gq * l[i] / (s.w[i] * s.w[i]);
+                    double wi = (double)s.w[i];
+                    double gq = (gb[i] - sb) / Q;
+                    double gl = gq / wi;
+                    gw[i] -= gq * l[i] / (wi * wi);
                     Gx += gl * glx[i];
                     Gy += gl * gly[i];
                 }
@@ -632,12 +638,13 @@ __global__ void k_rast_bwd_tri(const float4 *__restrict__ pos_clip, const int32_
         int corner = dr_corner(s.meta, i);
         float4 p = pc[vid[corner]];
         float xn = p.x / p.w, yn = p.y / p.w;
-        float gx = gsx[i] * hw / p.w;
-        float gy = -gsy[i] * hh / p.w;
-        float gww = (-gsx[i] * hw * xn + gsy[i] * hh * yn) / p.w + gw[i];
-        cg[corner * 3 + 0] = gx;
-        cg[corner * 3 + 1] = gy;
-        cg[corner * 3 + 2] = gww;
+        double w = p.w;
+        double gx = gsx[i] * hw / w;
+        double gy = -gsy[i] * hh / w;
+        double gww = (-gsx[i] * hw * xn + gsy[i] * hh * yn) / w + gw[i];
+        cg[corner * 3 + 0] = (float)gx;
+        cg[corner * 3 + 1] = (float)gy;
+        cg[corner * 3 + 2] = (float)gww;
     }
 }
 
