@@ -1,0 +1,273 @@
+#!/usr/bin/env python
+"""Forward+backward throughput of the Dressi rasterization hot path on one
+MI355X (gfx950).
+
+Workload (the configuration the headline metric is quoted on): a noisy
+icosphere of 40,962 vertices / 81,920 triangles seen by one 512x512 camera,
+spherical UVs on a 1024x1024 RGBA fp32 value-noise texture, hard
+rasterization (K=1), Phong shading, L2 loss against a render of a perturbed
+mesh and texture, backward to vertex positions and texels (texels through the
+inverse-UV gather).  All inputs are seeded and synthetic.
+
+One step = vertex normals + transform, rasterize, interpolate, texture,
+shade, blend, loss, and every adjoint.  "batched" replays the whole step as
+one captured hipGraph; "plain" issues the same calls eagerly (for multi-view
+configurations: one view per call).  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--profile-steps", type=int, default=20)
+    ap.add_argument("--only-graph", action="store_true",
+                    help="only the captured-step replays (for external profilers)")
+    return ap.parse_args()
+
+
+def scene_for(cfg):
+    from paper_2204_01386_amd import scenes
+    if cfg == 1:
+        return scenes.config1(), "icosphere s3 (642 v, 1,280 t), 1 view 128x128, per-vertex RGB, K=1, Lambert"
+    if cfg == 2:
+        return scenes.config2(), ("noisy icosphere s6 (40,962 v, 81,920 t), 1 view 512x512, "
+                                  "1024x1024 RGBA fp32 texture, K=1, Phong")
+    return scenes.config3(), ("noisy icosphere s6 (81,920 t), 16 views 512x512, 1024^2 RGBA texture + "
+                              "1024^2 normal map, 6x128^2 env map, HardSoftRas K=3 r=0.01, Phong+env")
+
+
+# ---------------------------------------------------------------------------
+# algorithmic bytes per launch of the main kernels (inputs read once and
+# outputs written once at their dtype; internal scratch is not counted)
+# ---------------------------------------------------------------------------
+def kernel_bytes(name, st, cov):
+    B, K, H, W = st.B, st.K, st.H, st.W
+    N = B * K * H * W             # fragment slots
+    P = B * H * W                 # pixels
+    Nc = cov                      # covered fragments
+    V, T, Cv = st.V, st.T, st.Cv
+    soft = st.r > 0
+    if name == "k_raster":
+        return N * (4 + 8 + (4 if soft else 0))
+    if name == "k_setup_count":
+        return B * V * 16 + T * 12
+    if name == "k_interp":
+        # one of the interpolations: the per-vertex attributes (Cv channels)
+        return N * (4 + 8) + N * 4 * Cv + V * Cv * 4 + T * 12
+    if name == "k_tex_fwd":
+        Ct = st.Ct
+        texels = min(st.tex.shape[0] * st.tex.shape[1], 4 * Nc)
+        return N * (4 + 8) + texels * Ct * 4 + N * Ct * 4
+    if name == "k_invuv_gather":
+        Ct = st.Ct
+        cells = st.tex.shape[0] * st.tex.shape[1]
+        S = B * K
+        return S * cells * 4 + cells * Ct * 4 + min(Nc, S * cells) * (8 + Ct * 4)
+    if name == "k_invuv_build":
+        S = B * K
+        cells = st.tex.shape[0] * st.tex.shape[1]
+        return N * (4 + 8) + min(Nc, S * cells) * 4
+    if name == "k_shade":
+        return N * 4 + N * 4 * (6 + st.Ct) + N * 12
+    if name == "k_shade_bwd":
+        return N * 4 + N * 4 * (6 + st.Ct) + N * 12 + N * 4 * (6 + st.Ct)
+    if name == "k_blend":
+        return N * (12 + 4 + (4 if soft else 0)) + P * (12 + 4 + 1)
+    if name == "k_blend_bwd":
+        return N * (12 + 4 + (4 if soft else 0)) + P * (1 + 12 + 4) + N * (12 + (4 if soft else 0))
+    if name == "k_rast_bwd_tri":
+        return Nc * (8 + (4 if soft else 0)) + B * V * 16 + T * 12 + B * T * 36
+    if name == "k_interp_bwd_tri":
+        return Nc * (8 + 4 * Cv) + B * T * 3 * Cv * 4
+    if name == "k_interp_bwd_bary":
+        return N * 4 + N * 4 * Cv + N * 8
+    if name == "k_tex_bwd_coord":
+        Ct = st.Ct
+        texels = min(st.tex.shape[0] * st.tex.shape[1], 4 * Nc)
+        return N * (4 + 8) + texels * Ct * 4 + N * Ct * 4 + N * 8
+    if name == "k_fragsort":
+        return N * 4
+    if name == "k_loss_l2":
+        return P * (12 + 4 + 16) + P * 16
+    return None
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (one MI355X per box); --gpus {args.gpus} is not "
+              f"supported. The path shards by views/instances; see the design notes.", file=sys.stderr)
+        sys.exit(2)
+    import ctypes as C
+
+    import numpy as np
+    import torch
+
+    from paper_2204_01386_amd import binding as Bd
+    from paper_2204_01386_amd.pipeline import Step, make_target
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    scene, desc = scene_for(args.config)
+    B = scene.mvp.shape[0]
+    tgt = make_target(scene)
+    st = Step(scene, target=tgt)
+    ctx = Bd.context()
+
+    # ---- warm-up (grows the scratch arena), then capture the step --------
+    for _ in range(3):
+        st.run()
+    torch.cuda.synchronize()
+    if ctx.check_status() != 0:
+        raise SystemExit("tile-bin capacity overflow during warm-up")
+    graph = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        st.run()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(graph):
+        st.run()
+    for _ in range(args.warmup):
+        graph.replay()
+    torch.cuda.synchronize()
+
+    # ---- batched: K replays of the captured step ---------------------------
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter()
+    e0.record()
+    for _ in range(args.steps):
+        graph.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter() - t_wall
+    ms_batched = e0.elapsed_time(e1) / args.steps
+    if args.only_graph:
+        print(json.dumps({"ms_per_step": ms_batched}))
+        return
+    if ctx.check_status() != 0:
+        raise SystemExit("tile-bin capacity overflow in the timed region")
+
+    # ---- plain: eager calls, one view per call -----------------------------
+    if B == 1:
+        plain_steps = [st]
+    else:
+        plain_steps = [Step(scene, views=slice(v, v + 1), target=None) for v in range(B)]
+        for v, ps in enumerate(plain_steps):
+            ps.target.copy_(tgt.rgba()[v:v + 1])
+    for _ in range(3):
+        for ps in plain_steps:
+            ps.run()
+    torch.cuda.synchronize()
+    n_plain = max(10, args.steps // 4)
+    e0.record()
+    for _ in range(n_plain):
+        for ps in plain_steps:
+            ps.run()
+    e1.record()
+    torch.cuda.synchronize()
+    ms_plain = e0.elapsed_time(e1) / n_plain
+
+    # ---- per-kernel timing (HIP events around every launch, eager) ---------
+    n_prof = args.profile_steps
+    Bd._lib.dressi_profile_start.argtypes = [C.c_int]
+    Bd._lib.dressi_profile_read.argtypes = [C.POINTER(C.c_char_p), C.POINTER(C.c_float), C.c_int]
+    cap = 200 * n_prof
+    Bd._lib.dressi_profile_start(cap)
+    for _ in range(n_prof):
+        st.run()
+    torch.cuda.synchronize()
+    names = (C.c_char_p * cap)()
+    ms = (C.c_float * cap)()
+    n = Bd._lib.dressi_profile_read(names, ms, cap)
+    Bd._lib.dressi_profile_start(0)
+    per = {}
+    for i in range(n):
+        k = names[i].decode()
+        tot, cnt = per.get(k, (0.0, 0))
+        per[k] = (tot + ms[i], cnt + 1)
+    table = sorted(((k, tot / n_prof, tot / cnt, cnt // n_prof) for k, (tot, cnt) in per.items()),
+                   key=lambda x: -x[1])
+    cov = int((st.tri_id >= 0).sum().item())
+    dom = next((row for row in table if kernel_bytes(row[0], st, cov) is not None), table[0])
+    dom_bytes = kernel_bytes(dom[0], st, cov)
+    achieved = dom_bytes / (dom[2] * 1e-3) / 1e9 if dom_bytes else None
+    kernel_rows = [{"kernel": k, "ms_per_step": round(a, 5), "ms_per_launch": round(b, 5),
+                    "launches_per_step": c,
+                    "alg_bytes": kernel_bytes(k, st, cov)} for k, a, b, c in table]
+
+    # ---- CPU baseline: the oracle's step on the same workload --------------
+    cpu = None
+    if not args.no_cpu:
+        from oracle import step as ostep
+        otgt = ostep.forward(scene, target=True)["rgba"]
+        t0 = time.perf_counter()
+        nrun = 0
+        while True:
+            o = ostep.forward(scene)
+            ostep.backward(scene, o, otgt)
+            nrun += 1
+            if time.perf_counter() - t0 > args.cpu_seconds or nrun >= 200:
+                break
+        tc = (time.perf_counter() - t0) / nrun
+        cpu = {"value": round(B * scene.H * scene.W / tc / 1e6, 4), "unit": "Mpix/s", "cores": 1,
+               "kind": "oracle",
+               "sample": f"{nrun} full fwd+bwd steps of the same workload (C oracle, fp64, "
+                         f"single thread), {tc * 1e3:.1f} ms/step"}
+
+    pix = B * scene.H * scene.W
+    res = {
+        "metric": "fwd+bwd Mpix/s & tris/s at 512^2 80k tris; batched vs plain speedup, %HBM roofline",
+        "value": round(pix / (ms_batched * 1e-3) / 1e6, 3),
+        "unit": "Mpix/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_batched, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded meshes, value-noise textures)",
+        "config": {"workload": desc, "views": B, "H": scene.H, "W": scene.W,
+                   "triangles": int(scene.tris.shape[0]), "vertices": int(scene.pos.shape[0]),
+                   "K": scene.K, "r": scene.r},
+        "tris_per_s": round(B * scene.tris.shape[0] / (ms_batched * 1e-3), 1),
+        "plain": {"ms_per_step": round(ms_plain, 5),
+                  "value": round(pix / (ms_plain * 1e-3) / 1e6, 3), "unit": "Mpix/s"},
+        "batched_vs_plain_speedup": round(ms_plain / ms_batched, 3),
+        "wall_s_timed": round(t_wall, 4),
+        "roofline": {"bound": "hbm", "kernel": dom[0],
+                     "achieved": round(achieved, 2) if achieved else None,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
+                     "traffic": None,
+                     "alg_bytes_per_launch": dom_bytes,
+                     "ms_per_launch": round(dom[2], 5)},
+        "cpu_baseline": cpu,
+        "kernels": kernel_rows,
+    }
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

@@ -84,6 +84,15 @@ size_t dressi_scratch_bytes(int B, int V, int T, int H, int W, int K, float r,
  * receives the capacity that call required (may be NULL). */
 int dressi_check_status(dressi_ctx *ctx, int64_t *needed, void *stream);
 
+/* Kernel timing for measurement: while on, every kernel launch of the library
+ * is bracketed by HIP events on its stream.  dressi_profile_start(n) turns it
+ * on for up to n launches (0 turns it off); dressi_profile_read waits for the
+ * recorded launches, returns their count and fills names[i] (static strings)
+ * and ms[i], then starts a new window.  Process-wide; not for use while a
+ * stream is being captured. */
+int dressi_profile_start(int max_launches);
+int dressi_profile_read(const char **names, float *ms, int max);
+
 /* ----------------------------------------------------------------------------
  * Rasterization (Algorithm 2, §3.4.2; the Shift equation; PeelDepth).
  *
@@ -134,12 +143,14 @@ int dressi_interpolate(dressi_ctx *ctx, const float *attr, int Ba, int Va, int C
                        const float *bary, int B, int K, int H, int W, float *out, void *stream);
 
 /* grad_attr [Ba,Va,C] (summed over views when Ba = 1) and grad_bary
- * [B,K,H,W,2]; either may be NULL.  Deterministic (sorted per-tile lists). */
+ * [B,K,H,W,2]; either may be NULL.  grad_bary_in (NULL = 0) is added to
+ * grad_bary, so several interpolations of one rasterization can chain their
+ * barycentric gradients.  Deterministic (sorted per-tile lists). */
 int dressi_interpolate_bwd(dressi_ctx *ctx, const float *attr, int Ba, int Va, int C,
                            const int32_t *attr_tris, int T, const int32_t *tri_id,
                            const float *bary, int B, int K, int H, int W,
-                           const float *grad_out, float *grad_attr, float *grad_bary,
-                           void *stream);
+                           const float *grad_out, const float *grad_bary_in, float *grad_attr,
+                           float *grad_bary, void *stream);
 
 /* ----------------------------------------------------------------------------
  * Bilinear texture sampling (the sampler behind GLSL texture(), §3.3.2).
@@ -186,6 +197,86 @@ int dressi_softras_bwd(dressi_ctx *ctx, const float *color, const float *dist,
                        const int32_t *tri_id, int B, int K, int H, int W, int Cc, float sigma,
                        const uint8_t *edge_mask, const float *grad_color, const float *grad_sil,
                        float *grad_layer_color, float *grad_dist, void *stream);
+
+
+/* ----------------------------------------------------------------------------
+ * The rest of one rendering step around the four stages above (the paper's
+ * decomposition I = f_pp(f_shade(f_rasterize(...))), §3.4.1, and the
+ * BuildRasterize listing): vertex transform, per-vertex attribute assembly
+ * with vertex normals, deferred shading of every layer, and the image loss.
+ * ------------------------------------------------------------------------- */
+
+/* pos_clip[b,v,:] = mvp[b] (4x4 row-major) applied to the column (p_v, 1).
+ * pos [V,3], mvp [B,4,4], pos_clip [B,V,4]. */
+int dressi_transform(dressi_ctx *ctx, const float *pos, const float *mvp, int B, int V,
+                     float *pos_clip, void *stream);
+/* grad_pos [V,3] = sum over views of mvp[b][:, :3]^T grad_clip[b,v] (views summed
+ * in order, deterministic). */
+int dressi_transform_bwd(dressi_ctx *ctx, const float *mvp, int B, int V, const float *grad_clip,
+                         float *grad_pos, void *stream);
+
+/* Per-vertex attribute rows out[v] = (n_v, p_v[, extra_v]) with C = 6 or 9,
+ * n_v = normalize(sum of (p1-p0) x (p2-p0) over the faces of v) (the
+ * listing's BuildNormalCompute; area-weighted, summed in corner order).
+ * extra [V,3] (a tangent, a colour, ...) may be NULL (then C = 6). */
+int dressi_vertex_attrs(dressi_ctx *ctx, const float *pos, const int32_t *tris, int V, int T,
+                        const float *extra, float *out, void *stream);
+/* grad_pos [V,3] from grad_out [V,C] through the normal and position columns,
+ * plus grad_pos_in (NULL = 0).  The gradient of `extra` is grad_out[:, 6:9]
+ * itself and is not written. */
+int dressi_vertex_attrs_bwd(dressi_ctx *ctx, const float *pos, const int32_t *tris, int V, int T,
+                            int C, const float *grad_out, const float *grad_pos_in,
+                            float *grad_pos, void *stream);
+
+#define DRESSI_SHADE_LAMBERT 0   /* c = a (0.1 + 0.9 max(0, n.l))                         */
+#define DRESSI_SHADE_PHONG 1     /* c = a_rgb (0.1 + 0.8 max(0,n.l)) + 0.2 a_a max(0,r.v)^32 */
+#define DRESSI_SHADE_PHONG_ENV 2 /* Phong + 0.5 a_a env(reflect(-v, n))                   */
+
+/* Per-fragment shading inputs: each is a pointer to rows of `stride` floats
+ * (so it can point into an interpolated attribute buffer) or NULL. */
+typedef struct {
+    const float *normal; int normal_stride;   /* interpolated normal (renormalised)    */
+    const float *pos; int pos_stride;         /* world position (Phong modes)          */
+    const float *tangent; int tangent_stride; /* tangent, for normal mapping           */
+    const float *nmap; int nmap_stride;       /* tangent-space normal-map sample       */
+    const float *albedo; int albedo_stride;   /* albedo rgb or rgba                    */
+    int albedo_channels;                      /* 3 or 4 (Phong modes need 4)           */
+    const float *env; int env_stride;         /* environment sample (PHONG_ENV)        */
+} dressi_frag_in;
+
+typedef struct {
+    float *normal; int normal_stride;
+    float *pos; int pos_stride;
+    float *tangent; int tangent_stride;
+    float *nmap; int nmap_stride;
+    float *albedo; int albedo_stride;
+    float *env; int env_stride;
+} dressi_frag_grad;
+
+/* Deferred shading of N = B*Npv fragments (view b = i / Npv, eye[b] its camera
+ * position, light direction (1,1,2)/sqrt(6), white).  The shading normal is
+ * normalize(normal), or, with tangent and nmap, normalize(m_x t^ + m_y b^ +
+ * m_z n^) with t^ = normalize(t - (t.n^) n^), b^ = n^ x t^.  Writes, when
+ * non-NULL: dir [N,3] = reflect(-v^, n') (the environment lookup direction)
+ * and color [N,3] (PHONG_ENV then needs in->env).  Fragments with
+ * tri_id < 0 give 0. */
+int dressi_shade(dressi_ctx *ctx, int mode, const dressi_frag_in *in, const float *eye,
+                 const int32_t *tri_id, int B, int64_t Npv, float *color, float *dir,
+                 void *stream);
+/* Backward of dressi_shade w.r.t. every non-NULL member of `grad` (rows of
+ * `stride` floats; members may point into one packed buffer).  grad_dir
+ * (NULL = 0) is the gradient of `dir`; the environment-sample gradient does
+ * not depend on it, so it can be taken first (all other members NULL). */
+int dressi_shade_bwd(dressi_ctx *ctx, int mode, const dressi_frag_in *in, const float *eye,
+                     const int32_t *tri_id, int B, int64_t Npv, const float *grad_color,
+                     const float *grad_dir, const dressi_frag_grad *grad, void *stream);
+
+/* L = mean over B*H*W*4 of ((color, sil) - target)^2.  color [B,H,W,3],
+ * sil [B,H,W], target [B,H,W,4]; writes loss [1] (device, fixed-order
+ * reduction) and, when non-NULL, grad_color and grad_sil of L. */
+int dressi_loss_l2(dressi_ctx *ctx, const float *color, const float *sil, const float *target,
+                   int B, int H, int W, float *loss, float *grad_color, float *grad_sil,
+                   void *stream);
 
 #ifdef __cplusplus
 }

@@ -430,3 +430,30 @@ def loss_l2(color, sil, target):
     f.argtypes = [C.c_void_p] * 3 + [C.c_int64] + [C.c_void_p] * 3
     _check(f(_p(c), _p(s), _p(t), s.size, C.byref(L), _p(gc), _p(gs)), "loss_l2")
     return L.value, gc, gs
+
+
+def transform_f32(pos, mvp):
+    p = _f32(pos)
+    m = _f32(mvp)
+    if m.ndim == 2:
+        m = m[None]
+    B, V = m.shape[0], p.shape[0]
+    out = np.empty((B, V, 4), np.float32)
+    f = lib().orc_transform_f32
+    f.argtypes = [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_void_p]
+    _check(f(_p(p), _p(m), B, V, _p(out)), "transform_f32")
+    return out
+
+
+def interpolate_f32(attr, attr_tris, tri_id, bary):
+    a = _f32(attr)
+    Va, Cc = a.shape
+    tid = _i32(tri_id)
+    at = _i32(attr_tris)
+    out = np.empty(tid.shape + (Cc,), np.float32)
+    f = lib().orc_interpolate_f32
+    f.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p,
+                  C.c_int64, C.c_void_p]
+    _check(f(_p(a), Va, Cc, _p(at), at.shape[0], _p(tid), _p(_f32(bary)), tid.size, _p(out)),
+           "interpolate_f32")
+    return out

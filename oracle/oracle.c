@@ -1382,3 +1382,55 @@ int orc_loss_l2(const double *color, const double *sil, const double *target, in
     *loss = s * inv;
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Single-precision versions of the two value computations that feed        */
+/* discrete decisions downstream: clip coordinates (snapping) and texture   */
+/* coordinates (texel and inverse-UV cell selection).  Both sides compute   */
+/* them in float with this operation order, so the decisions coincide.      */
+/* ------------------------------------------------------------------------ */
+
+/* o_r = ((M_r0 x + M_r1 y) + M_r2 z) + M_r3, no fused multiply-add */
+int orc_transform_f32(const float *pos, const float *mvp, int B, int V, float *out)
+{
+    for (int b = 0; b < B; b++) {
+        const float *M = mvp + 16 * (int64_t)b;
+        for (int v = 0; v < V; v++) {
+            const float *p = pos + 3 * (int64_t)v;
+            float *o = out + 4 * ((int64_t)b * V + v);
+            for (int r = 0; r < 4; r++) {
+                float t0 = M[4 * r] * p[0];
+                float t1 = M[4 * r + 1] * p[1];
+                float t2 = M[4 * r + 2] * p[2];
+                float s = t0 + t1;
+                s = s + t2;
+                o[r] = s + M[4 * r + 3];
+            }
+        }
+    }
+    return 0;
+}
+
+/* out = (b0 a0 + b1 a1) + b2 a2 with b2 = (1 - b0) - b1, all float */
+int orc_interpolate_f32(const float *attr, int Va, int C, const int32_t *attr_tris, int T,
+                        const int32_t *tri_id, const float *bary, int64_t N, float *out)
+{
+    for (int64_t o = 0; o < N; o++) {
+        float *y = out + o * C;
+        int32_t t = tri_id[o];
+        if (t < 0 || t >= T) { for (int c = 0; c < C; c++) y[c] = 0.0f; continue; }
+        const int32_t *tv = attr_tris + 3 * (int64_t)t;
+        float w0 = bary[2 * o], w1 = bary[2 * o + 1];
+        float w2 = 1.0f - w0;
+        w2 = w2 - w1;
+        for (int c = 0; c < C; c++) {
+            float a = w0 * attr[(int64_t)tv[0] * C + c];
+            float b = w1 * attr[(int64_t)tv[1] * C + c];
+            float d = w2 * attr[(int64_t)tv[2] * C + c];
+            float s = a + b;
+            y[c] = s + d;
+        }
+    }
+    (void)Va;
+    return 0;
+}

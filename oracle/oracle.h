@@ -85,4 +85,7 @@ int orc_shade_bwd(int mode, const double *n, const double *pos, const double *al
                   const double *g, double *gn, double *gpos, double *galb, double *genv);
 int orc_loss_l2(const double *color, const double *sil, const double *target, int64_t Npix,
                 double *loss, double *grad_color, double *grad_sil);
+int orc_transform_f32(const float *pos, const float *mvp, int B, int V, float *out);
+int orc_interpolate_f32(const float *attr, int Va, int C, const int32_t *attr_tris, int T,
+                        const int32_t *tri_id, const float *bary, int64_t N, float *out);
 #endif

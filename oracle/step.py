@@ -1,0 +1,140 @@
+"""The oracle's end-to-end step (test infrastructure): the same decomposition
+as the GPU step (§3.4.1: transform and vertex normals, rasterization,
+interpolation, texture sampling, deferred shading, HardSoftRas blend, L2
+loss, then the adjoints in reverse), composed from the oracle's own
+functions in double precision.  Two values that feed discrete decisions are
+computed in single precision with the kernel's operation order (the clip
+coordinates, which are snapped, and the texture coordinates, whose texel and
+inverse-UV cell are selected), so that those decisions coincide."""
+from __future__ import annotations
+
+import numpy as np
+
+import oracle as O
+
+MODES = {"lambert": O.SHADE_LAMBERT, "phong": O.SHADE_PHONG, "phong_env": O.SHADE_PHONG_ENV}
+
+
+def _params(scene, target):
+    pos = scene.target_pos if target and scene.target_pos is not None else scene.pos
+    color = None
+    tex = None
+    if scene.shading == "lambert":
+        color = scene.target_color if target and scene.target_color is not None else scene.color
+    else:
+        tex = scene.target_tex if target and scene.target_tex is not None else scene.tex
+        if scene.nmap is not None:
+            tex = np.concatenate([tex, scene.nmap], -1)
+    return pos, color, tex
+
+
+def forward(scene, views=None, target=False):
+    sl = slice(None) if views is None else views
+    mvp = scene.mvp[sl].astype(np.float32)
+    eye = scene.eyes[sl].astype(np.float64)
+    mode = MODES[scene.shading]
+    pos, color, tex = _params(scene, target)
+    pos32 = np.ascontiguousarray(pos, np.float32)
+    tris = scene.tris
+    H, W, K, r = scene.H, scene.W, scene.K, float(scene.r)
+    st = {"mode": mode, "mvp": mvp, "eye": eye, "pos": pos32.astype(np.float64), "tex": tex,
+          "color_param": color}
+    n = O.vertex_normals(st["pos"], tris)
+    extra = None
+    if mode == O.SHADE_LAMBERT:
+        extra = np.asarray(color, np.float64)
+    elif mode == O.SHADE_PHONG_ENV:
+        extra = np.asarray(scene.extra["tangent"], np.float64)
+    vattr = np.concatenate([n, st["pos"]] + ([extra] if extra is not None else []), 1)
+    pc = O.transform_f32(pos32, mvp)
+    tid, hard, bary, dist = O.rasterize(pc, tris, H, W, K=K, r=r)
+    gb = O.interpolate(vattr, tris, tid, bary)
+    st.update(vattr=vattr, pc=pc, tid=tid, hard=hard, bary=bary, dist=dist if r > 0 else None, gbuf=gb)
+    nrm = gb[..., 0:3]
+    p = gb[..., 3:6]
+    if mode == O.SHADE_LAMBERT:
+        albedo = gb[..., 6:9]
+        shade_n = nrm
+    else:
+        uv = O.interpolate_f32(scene.uv, scene.uv_tris, tid, bary.astype(np.float32))
+        samp = O.texture(tex, uv, tid)
+        st.update(uv=uv, samp=samp)
+        albedo = samp[..., 0:4]
+        shade_n = nrm
+    env_s = None
+    if mode == O.SHADE_PHONG_ENV:
+        shade_n = O.normal_map(nrm, gb[..., 6:9], samp[..., 4:7], tid)
+        d = O.reflect(shade_n, p, eye, tid)
+        env_s = O.texture(scene.env, d.astype(np.float32), tid, kind=O.TEX_CUBE)
+        st.update(shade_n=shade_n, dir=d, env_s=env_s)
+    col = O.shade(mode, shade_n, p if mode != O.SHADE_LAMBERT else None, albedo, env_s, eye, tid)
+    sigma = r / 7.0 if r > 0 else 1.0
+    blend = O.BLEND_HSR if r > 0 else O.BLEND_HARD
+    oc, os_, E = O.softras(col, st["dist"], tid, sigma, r, blend)
+    st.update(layer_color=col, albedo=albedo, color=oc, sil=os_, E=E, sigma=sigma)
+    st["rgba"] = np.concatenate([oc, os_[..., None]], -1)
+    return st
+
+
+def backward(scene, st, target_rgba):
+    mode = st["mode"]
+    tid = st["tid"]
+    tris = scene.tris
+    L, g_c, g_s = O.loss_l2(st["color"], st["sil"], target_rgba)
+    gl, gd = O.softras_bwd(st["layer_color"], st["dist"], tid, st["sigma"], st["E"], g_c, g_s)
+    gb = st["gbuf"]
+    nrm, p = gb[..., 0:3], gb[..., 3:6]
+    eye = st["eye"]
+    g_gbuf = np.zeros_like(gb)
+    out = {"loss": L}
+    if mode == O.SHADE_LAMBERT:
+        gn, _, ga, _ = O.shade_bwd(mode, nrm, None, st["albedo"], None, eye, tid, gl)
+        g_gbuf[..., 0:3] = gn
+        g_gbuf[..., 6:9] = ga
+    elif mode == O.SHADE_PHONG:
+        gn, gp, ga, _ = O.shade_bwd(mode, nrm, p, st["albedo"], None, eye, tid, gl)
+        g_gbuf[..., 0:3] = gn
+        g_gbuf[..., 3:6] = gp
+        g_samp = ga
+    else:
+        gnp, gp, ga, ge = O.shade_bwd(mode, st["shade_n"], p, st["albedo"], st["env_s"], eye, tid, gl)
+        d32 = st["dir"].astype(np.float32)
+        gdir = O.texture_bwd_coord(scene.env, d32, ge, tid, kind=O.TEX_CUBE)
+        out["env"] = O.texture_bwd_tex(scene.env.shape, d32.reshape((-1,) + d32.shape[2:]),
+                                       tid.reshape((-1,) + tid.shape[2:]),
+                                       ge.reshape((-1,) + ge.shape[2:]), kind=O.TEX_CUBE)
+        gnp2, gp2 = O.reflect_bwd(st["shade_n"], p, eye, tid, gdir)
+        gn, gt, gm = O.normal_map_bwd(nrm, gb[..., 6:9], st["samp"][..., 4:7], tid, gnp + gnp2)
+        g_gbuf[..., 0:3] = gn
+        g_gbuf[..., 3:6] = gp + gp2
+        g_gbuf[..., 6:9] = gt
+        g_samp = np.concatenate([ga, gm], -1)
+    g_bary_uv = 0.0
+    if mode != O.SHADE_LAMBERT:
+        uv = st["uv"]
+        S = tid.shape[0] * tid.shape[1]
+        rs = lambda a: a.reshape((S,) + a.shape[2:])
+        g_uv = O.texture_bwd_coord(st["tex"], uv, g_samp, tid)
+        out["tex"] = O.texture_bwd_tex(st["tex"].shape, rs(uv), rs(tid), rs(g_samp))
+        _, g_bary_uv = O.interpolate_bwd(scene.uv, scene.uv_tris, tid, st["bary"], g_uv)
+    g_vattr, g_bary = O.interpolate_bwd(st["vattr"], tris, tid, st["bary"], g_gbuf)
+    g_bary = g_bary + g_bary_uv
+    g_clip = O.rasterize_bwd(st["pc"], tris, tid, st["hard"], g_bary, O_grad_dist(gd, st))
+    g_pos = O.transform_bwd(st["mvp"], g_clip)
+    g_pos += O.vertex_normals_bwd(st["pos"], tris, g_vattr[:, 0:3]) + g_vattr[:, 3:6]
+    out["pos"] = g_pos
+    if mode == O.SHADE_LAMBERT:
+        out["color"] = g_vattr[:, 6:9]
+    return out
+
+
+def O_grad_dist(gd, st):
+    return gd if st["dist"] is not None else None
+
+
+def step(scene, views=None):
+    """Forward of the target, forward of the current scene, loss and backward."""
+    tgt = forward(scene, views, target=True)
+    st = forward(scene, views)
+    grads = backward(scene, st, tgt["rgba"])
+    return st, tgt, grads

@@ -38,6 +38,22 @@ class TexDesc(C.Structure):
 
 
 _vp, _i, _f, _i64, _sz = C.c_void_p, C.c_int, C.c_float, C.c_int64, C.c_size_t
+
+SHADE_LAMBERT, SHADE_PHONG, SHADE_PHONG_ENV = 0, 1, 2
+
+
+class FragIn(C.Structure):
+    """dressi_frag_in: per-fragment shading inputs as (pointer, row stride)."""
+    _fields_ = [("normal", _vp), ("normal_stride", _i), ("pos", _vp), ("pos_stride", _i),
+                ("tangent", _vp), ("tangent_stride", _i), ("nmap", _vp), ("nmap_stride", _i),
+                ("albedo", _vp), ("albedo_stride", _i), ("albedo_channels", _i),
+                ("env", _vp), ("env_stride", _i)]
+
+
+class FragGrad(C.Structure):
+    _fields_ = [("normal", _vp), ("normal_stride", _i), ("pos", _vp), ("pos_stride", _i),
+                ("tangent", _vp), ("tangent_stride", _i), ("nmap", _vp), ("nmap_stride", _i),
+                ("albedo", _vp), ("albedo_stride", _i), ("env", _vp), ("env_stride", _i)]
 _SIG = {
     "dressi_create": [C.POINTER(C.c_void_p), _i],
     "dressi_destroy": [_vp],
@@ -47,11 +63,18 @@ _SIG = {
     "dressi_rasterize_bwd": [_vp, _vp, _vp, _i, _i, _i, _i, _i, _i, _f, _i, _vp, _vp, _vp, _vp, _vp],
     "dressi_interpolate": [_vp, _vp, _i, _i, _i, _vp, _i, _vp, _vp, _i, _i, _i, _i, _vp, _vp],
     "dressi_interpolate_bwd": [_vp, _vp, _i, _i, _i, _vp, _i, _vp, _vp, _i, _i, _i, _i, _vp, _vp,
-                               _vp, _vp],
+                               _vp, _vp, _vp],
     "dressi_texture": [_vp, _vp, C.POINTER(TexDesc), _vp, _vp, _i, _i, _i, _vp, _vp],
     "dressi_texture_bwd": [_vp, _vp, C.POINTER(TexDesc), _vp, _vp, _i, _i, _i, _vp, _vp, _vp, _vp],
     "dressi_softras": [_vp, _vp, _vp, _vp, _i, _i, _i, _i, _i, _f, _f, _i, _vp, _vp, _vp, _vp],
     "dressi_softras_bwd": [_vp, _vp, _vp, _vp, _i, _i, _i, _i, _i, _f, _vp, _vp, _vp, _vp, _vp, _vp],
+    "dressi_transform": [_vp, _vp, _vp, _i, _i, _vp, _vp],
+    "dressi_transform_bwd": [_vp, _vp, _i, _i, _vp, _vp, _vp],
+    "dressi_vertex_attrs": [_vp, _vp, _vp, _i, _i, _vp, _vp, _vp],
+    "dressi_vertex_attrs_bwd": [_vp, _vp, _vp, _i, _i, _i, _vp, _vp, _vp, _vp],
+    "dressi_shade": [_vp, _i, _vp, _vp, _vp, _i, _i64, _vp, _vp, _vp],
+    "dressi_shade_bwd": [_vp, _i, _vp, _vp, _vp, _i, _i64, _vp, _vp, _vp, _vp],
+    "dressi_loss_l2": [_vp, _vp, _vp, _vp, _i, _i, _i, _vp, _vp, _vp, _vp],
 }
 for _name, _args in _SIG.items():
     fn = getattr(_lib, _name)
@@ -188,7 +211,8 @@ def dressi_interpolate(attr, attr_tris, tri_id, bary):
     return out
 
 
-def dressi_interpolate_bwd(attr, attr_tris, tri_id, bary, grad_out, need_attr=True, need_bary=True):
+def dressi_interpolate_bwd(attr, attr_tris, tri_id, bary, grad_out, need_attr=True, need_bary=True,
+                           grad_bary_in=None):
     a = _need(_attr3(attr), torch.float32, "attr")
     _need(grad_out, torch.float32, "grad_out")
     Ba, Va, Cc = a.shape
@@ -198,8 +222,8 @@ def dressi_interpolate_bwd(attr, attr_tris, tri_id, bary, grad_out, need_attr=Tr
     ctx = context(a.device.index)
     ctx.check(_lib.dressi_interpolate_bwd(ctx.handle, _ptr(a), Ba, Va, Cc, _ptr(attr_tris),
                                           attr_tris.shape[0], _ptr(tri_id), _ptr(bary), B, K, H, W,
-                                          _ptr(grad_out), _ptr(ga), _ptr(gb), _stream()),
-              "dressi_interpolate_bwd")
+                                          _ptr(grad_out), _ptr(grad_bary_in), _ptr(ga), _ptr(gb),
+                                          _stream()), "dressi_interpolate_bwd")
     if ga is not None and attr.dim() == 2:
         ga = ga[0]
     return ga, gb
@@ -277,3 +301,111 @@ def dressi_softras_bwd(color, dist, tri_id, sigma, edge_mask, grad_color, grad_s
                                       _ptr(grad_sil), _ptr(gl), _ptr(gd), _stream()),
               "dressi_softras_bwd")
     return gl, gd
+
+
+def dressi_transform(pos, mvp):
+    _need(pos, torch.float32, "pos")
+    _need(mvp, torch.float32, "mvp")
+    B, V = mvp.shape[0], pos.shape[0]
+    out = torch.empty((B, V, 4), dtype=torch.float32, device=pos.device)
+    ctx = context(pos.device.index)
+    ctx.check(_lib.dressi_transform(ctx.handle, _ptr(pos), _ptr(mvp), B, V, _ptr(out), _stream()),
+              "dressi_transform")
+    return out
+
+
+def dressi_transform_bwd(mvp, grad_clip):
+    _need(grad_clip, torch.float32, "grad_clip")
+    B, V, _ = grad_clip.shape
+    out = torch.empty((V, 3), dtype=torch.float32, device=grad_clip.device)
+    ctx = context(grad_clip.device.index)
+    ctx.check(_lib.dressi_transform_bwd(ctx.handle, _ptr(mvp), B, V, _ptr(grad_clip), _ptr(out),
+                                        _stream()), "dressi_transform_bwd")
+    return out
+
+
+def dressi_vertex_attrs(pos, tris, extra=None):
+    _need(pos, torch.float32, "pos")
+    _need(tris, torch.int32, "tris")
+    V, T = pos.shape[0], tris.shape[0]
+    C_ = 9 if extra is not None else 6
+    out = torch.empty((V, C_), dtype=torch.float32, device=pos.device)
+    ctx = context(pos.device.index)
+    ctx.check(_lib.dressi_vertex_attrs(ctx.handle, _ptr(pos), _ptr(tris), V, T, _ptr(extra), _ptr(out),
+                                       _stream()), "dressi_vertex_attrs")
+    return out
+
+
+def dressi_vertex_attrs_bwd(pos, tris, grad_out, grad_pos_in=None):
+    _need(grad_out, torch.float32, "grad_out")
+    V, T = pos.shape[0], tris.shape[0]
+    out = torch.empty((V, 3), dtype=torch.float32, device=pos.device)
+    ctx = context(pos.device.index)
+    ctx.check(_lib.dressi_vertex_attrs_bwd(ctx.handle, _ptr(pos), _ptr(tris), V, T, grad_out.shape[1],
+                                           _ptr(grad_out), _ptr(grad_pos_in), _ptr(out), _stream()),
+              "dressi_vertex_attrs_bwd")
+    return out
+
+
+def _col(t, off=0):
+    """(pointer to column `off` of a row-major tensor, row stride in floats)."""
+    if t is None:
+        return None, 0
+    return C.c_void_p(t.data_ptr() + 4 * off), int(t.shape[-1])
+
+
+def frag_in(normal, pos=None, tangent=None, nmap=None, albedo=None, env=None):
+    """Each argument is (tensor, column offset) or None."""
+    f = FragIn()
+    for name, v in (("normal", normal), ("pos", pos), ("tangent", tangent), ("nmap", nmap),
+                    ("albedo", albedo), ("env", env)):
+        if v is None:
+            continue
+        t, off = v
+        p, st = _col(t, off)
+        setattr(f, name, p)
+        setattr(f, name + "_stride", st)
+    if albedo is not None:
+        t, off = albedo
+        f.albedo_channels = min(4, t.shape[-1] - off)
+    return f
+
+
+def frag_grad(**kw):
+    g = FragGrad()
+    for name, v in kw.items():
+        if v is None:
+            continue
+        t, off = v
+        p, st = _col(t, off)
+        setattr(g, name, p)
+        setattr(g, name + "_stride", st)
+    return g
+
+
+def dressi_shade(mode, fin, eye, tri_id, color=None, dir=None):
+    B = tri_id.shape[0]
+    Npv = tri_id.numel() // B
+    ctx = context(tri_id.device.index)
+    ctx.check(_lib.dressi_shade(ctx.handle, mode, C.byref(fin), _ptr(eye), _ptr(tri_id), B, Npv,
+                                _ptr(color), _ptr(dir), _stream()), "dressi_shade")
+
+
+def dressi_shade_bwd(mode, fin, eye, tri_id, grad_color, grad_dir, fgrad):
+    B = tri_id.shape[0]
+    Npv = tri_id.numel() // B
+    ctx = context(tri_id.device.index)
+    ctx.check(_lib.dressi_shade_bwd(ctx.handle, mode, C.byref(fin), _ptr(eye), _ptr(tri_id), B, Npv,
+                                    _ptr(grad_color), _ptr(grad_dir), C.byref(fgrad), _stream()),
+              "dressi_shade_bwd")
+
+
+def dressi_loss_l2(color, sil, target, loss=None, grad_color=None, grad_sil=None):
+    B, H, W = sil.shape
+    if loss is None:
+        loss = torch.empty(1, dtype=torch.float32, device=sil.device)
+    ctx = context(sil.device.index)
+    ctx.check(_lib.dressi_loss_l2(ctx.handle, _ptr(color), _ptr(sil), _ptr(target), B, H, W,
+                                  _ptr(loss), _ptr(grad_color), _ptr(grad_sil), _stream()),
+              "dressi_loss_l2")
+    return loss

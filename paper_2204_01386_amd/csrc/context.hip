@@ -106,3 +106,70 @@ extern "C" int dressi_check_status(dressi_ctx *ctx, int64_t *needed, void *strea
     }
     return DRESSI_OK;
 }
+
+// ---------------------------------------------------------------------------
+// kernel timing (eager runs only; never enable while capturing a graph)
+// ---------------------------------------------------------------------------
+namespace {
+struct Prof {
+    bool on = false;
+    int cap = 0, used = 0;
+    hipEvent_t *ev = nullptr;
+    const char **names = nullptr;
+};
+Prof g_prof;
+
+void prof_free() {
+    for (int i = 0; i < 2 * g_prof.cap; i++) (void)hipEventDestroy(g_prof.ev[i]);
+    delete[] g_prof.ev;
+    delete[] g_prof.names;
+    g_prof = Prof();
+}
+}  // namespace
+
+int dr_prof_begin(const char *name, hipStream_t s) {
+    if (!g_prof.on || g_prof.used >= g_prof.cap) return -1;
+    int i = g_prof.used++;
+    g_prof.names[i] = name;
+    (void)hipEventRecord(g_prof.ev[2 * i], s);
+    return i;
+}
+
+void dr_prof_end(int slot, hipStream_t s) {
+    if (slot >= 0) (void)hipEventRecord(g_prof.ev[2 * slot + 1], s);
+}
+
+extern "C" int dressi_profile_start(int max_launches) {
+    prof_free();
+    if (max_launches <= 0) return DRESSI_OK;
+    g_prof.ev = new (std::nothrow) hipEvent_t[2 * (size_t)max_launches];
+    g_prof.names = new (std::nothrow) const char *[max_launches];
+    if (!g_prof.ev || !g_prof.names) {
+        prof_free();
+        return DRESSI_ENOMEM;
+    }
+    for (int i = 0; i < 2 * max_launches; i++) {
+        if (hipEventCreate(&g_prof.ev[i]) != hipSuccess) {
+            g_prof.cap = i / 2;
+            prof_free();
+            return DRESSI_EHIP;
+        }
+        g_prof.cap = (i + 1) / 2;
+    }
+    g_prof.cap = max_launches;
+    g_prof.on = true;
+    return DRESSI_OK;
+}
+
+extern "C" int dressi_profile_read(const char **names, float *ms, int max) {
+    int n = g_prof.used < max ? g_prof.used : max;
+    for (int i = 0; i < n; i++) {
+        if (hipEventSynchronize(g_prof.ev[2 * i + 1]) != hipSuccess) return DRESSI_EHIP;
+        float t = 0.0f;
+        if (hipEventElapsedTime(&t, g_prof.ev[2 * i], g_prof.ev[2 * i + 1]) != hipSuccess) return DRESSI_EHIP;
+        names[i] = g_prof.names[i];
+        ms[i] = t;
+    }
+    g_prof.used = 0;
+    return n;
+}

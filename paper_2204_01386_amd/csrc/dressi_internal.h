@@ -32,6 +32,18 @@ int dressi_hip_check(dressi_ctx *ctx, hipError_t e, const char *what);
 int dressi_scratch(dressi_ctx *ctx, size_t bytes, hipStream_t stream);
 int dressi_launch_check(dressi_ctx *ctx, const char *what);
 
+// Optional per-kernel timing with HIP events (eager runs only): every launch
+// goes through DR_LAUNCH, which brackets it with event records while the
+// profiler is on (dressi_profile_start) and costs one branch otherwise.
+int dr_prof_begin(const char *name, hipStream_t s);
+void dr_prof_end(int slot, hipStream_t s);
+#define DR_LAUNCH(NAME, KERN, GRID, BLOCK, SHMEM, STREAM, ...)                  \
+    do {                                                                        \
+        int dr_ps_ = dr_prof_begin(NAME, STREAM);                               \
+        hipLaunchKernelGGL(KERN, dim3(GRID), dim3(BLOCK), SHMEM, STREAM, __VA_ARGS__); \
+        dr_prof_end(dr_ps_, STREAM);                                            \
+    } while (0)
+
 // Bump allocator over the arena: carve(n) returns 256-byte aligned offsets.
 struct Carver {
     size_t off = 0;
@@ -95,7 +107,8 @@ __host__ __device__ static inline int tiles_y(int H) { return (H + DRESSI_TILE -
 
 // ---------------------------------------------------------------------------
 // Triangle setup shared by the forward and backward kernels (device code).
-// The arithmetic order below is the contract the oracle mirrors:
+// The arithmetic order below is part of the interface contract (the decisions
+// it feeds must be reproducible by any conforming implementation):
 //   x_px = (x/w + 1) * (W/2), y_px = (1 - y/w) * (H/2) in float, snapped with
 //   round-to-nearest-even to 1/256 px; twice the signed area in int64; the
 //   vertex order is normalised so the area is positive (1 <-> 2 swapped);

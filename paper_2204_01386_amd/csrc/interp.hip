@@ -59,7 +59,7 @@ extern "C" int dressi_interpolate(dressi_ctx *ctx, const float *attr, int Ba, in
     if (n == 0) return DRESSI_OK;
     if (!out) return dressi_fail(ctx, DRESSI_EINVAL, "interpolate: null out");
     hipStream_t st = (hipStream_t)stream;
-    k_interp<<<(int)((n + 255) / 256), 256, 0, st>>>(attr, Ba, Va, C, attr_tris, T, tri_id,
+    DR_LAUNCH("k_interp", (k_interp), (int)((n + 255) / 256), 256, 0, st, attr, Ba, Va, C, attr_tris, T, tri_id,
                                                      reinterpret_cast<const float2 *>(bary),
                                                      (int64_t)K * H * W, n, out);
     return dressi_launch_check(ctx, "interpolate");
@@ -69,7 +69,8 @@ extern "C" int dressi_interpolate(dressi_ctx *ctx, const float *attr, int Ba, in
 __global__ void k_interp_bwd_bary(const float *__restrict__ attr, int Ba, int Va, int C,
                                   const int32_t *__restrict__ attr_tris, int T,
                                   const int32_t *__restrict__ tri_id, int64_t per_view, int64_t n,
-                                  const float *__restrict__ grad_out, float2 *__restrict__ grad_bary) {
+                                  const float *__restrict__ grad_out, const float2 *__restrict__ gb_in,
+                                  float2 *__restrict__ grad_bary) {
     int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (o >= n) return;
     int t = tri_id[o];
@@ -79,8 +80,9 @@ __global__ void k_interp_bwd_bary(const float *__restrict__ attr, int Ba, int Va
         v1 = attr_tris[3 * (int64_t)t + 1];
         v2 = attr_tris[3 * (int64_t)t + 2];
     }
+    float2 acc = gb_in ? gb_in[o] : make_float2(0.0f, 0.0f);
     if (v0 < 0 || v0 >= Va || v1 < 0 || v1 >= Va || v2 < 0 || v2 >= Va) {
-        grad_bary[o] = make_float2(0.0f, 0.0f);
+        grad_bary[o] = acc;
         return;
     }
     int b = (int)(o / per_view);
@@ -93,7 +95,7 @@ __global__ void k_interp_bwd_bary(const float *__restrict__ attr, int Ba, int Va
         g0 += gc * (a0[c] - a2[c]);
         g1 += gc * (a1[c] - a2[c]);
     }
-    grad_bary[o] = make_float2(g0, g1);
+    grad_bary[o] = make_float2(acc.x + g0, acc.y + g1);
 }
 
 // per (view or shared, triangle, channel chunk): sum over fragments of b_i g
@@ -171,17 +173,17 @@ __global__ void k_interp_vertex_gather(const float *__restrict__ corner_grad, Ad
 extern "C" int dressi_interpolate_bwd(dressi_ctx *ctx, const float *attr, int Ba, int Va, int C,
                                       const int32_t *attr_tris, int T, const int32_t *tri_id,
                                       const float *bary, int B, int K, int H, int W,
-                                      const float *grad_out, float *grad_attr, float *grad_bary,
-                                      void *stream) {
+                                      const float *grad_out, const float *grad_bary_in,
+                                      float *grad_attr, float *grad_bary, void *stream) {
     int rc = check_interp(ctx, attr, Ba, Va, C, attr_tris, T, tri_id, bary, B, K, H, W);
     if (rc) return rc;
     int64_t n = (int64_t)B * K * H * W;
     if (n > 0 && !grad_out) return dressi_fail(ctx, DRESSI_EINVAL, "interpolate_bwd: null grad_out");
     hipStream_t st = (hipStream_t)stream;
     if (grad_bary && n > 0)
-        k_interp_bwd_bary<<<(int)((n + 255) / 256), 256, 0, st>>>(
+        DR_LAUNCH("k_interp_bwd_bary", (k_interp_bwd_bary), (int)((n + 255) / 256), 256, 0, st, 
             attr, Ba, Va, C, attr_tris, T, tri_id, (int64_t)K * H * W, n, grad_out,
-            reinterpret_cast<float2 *>(grad_bary));
+            reinterpret_cast<const float2 *>(grad_bary_in), reinterpret_cast<float2 *>(grad_bary));
     if (grad_attr && Va > 0) {
         Carver c;
         size_t o_fl = c.take(dressi_fraglists_bytes(B, H, W, K));
@@ -201,11 +203,11 @@ extern "C" int dressi_interpolate_bwd(dressi_ctx *ctx, const float *attr, int Ba
         int64_t ntri = (int64_t)Ba * T;
         if (ntri > 0) {
             dim3 g((unsigned)((ntri + 127) / 128), (unsigned)((C + IB_CH - 1) / IB_CH));
-            k_interp_bwd_tri<<<g, 128, 0, st>>>(B, Ba, T, K, H, W, C, tiles_x(W), fl, tt,
+            DR_LAUNCH("k_interp_bwd_tri", (k_interp_bwd_tri), g, 128, 0, st, B, Ba, T, K, H, W, C, tiles_x(W), fl, tt,
                                                  reinterpret_cast<const float2 *>(bary), grad_out, cg);
         }
         int64_t ng = (int64_t)Ba * Va * C;
-        k_interp_vertex_gather<<<(int)((ng + 255) / 256), 256, 0, st>>>(cg, adj, Ba, Va, T, C,
+        DR_LAUNCH("k_interp_vertex_gather", (k_interp_vertex_gather), (int)((ng + 255) / 256), 256, 0, st, cg, adj, Ba, Va, T, C,
                                                                           grad_attr);
     }
     return dressi_launch_check(ctx, "interpolate_bwd");

@@ -25,12 +25,12 @@ static int fill_grid(int64_t n) {
 
 void dressi_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s) {
     if (n <= 0) return;
-    k_fill_i32<<<fill_grid(n), 256, 0, s>>>(p, v, n);
+    DR_LAUNCH("k_fill_i32", (k_fill_i32), fill_grid(n), 256, 0, s, p, v, n);
 }
 
 void dressi_fill_f32(float *p, float v, int64_t n, hipStream_t s) {
     if (n <= 0) return;
-    k_fill_f32<<<fill_grid(n), 256, 0, s>>>(p, v, n);
+    DR_LAUNCH("k_fill_f32", (k_fill_f32), fill_grid(n), 256, 0, s, p, v, n);
 }
 
 // ---------------------------------------------------------------------------
@@ -131,9 +131,9 @@ void dressi_exclusive_scan(const int32_t *in, int32_t *out, int64_t n, void *tmp
     }
     int nb = (int)((n + SCAN_CHUNK - 1) / SCAN_CHUNK);
     int32_t *sums = static_cast<int32_t *>(tmp);
-    k_scan_reduce<<<nb, SCAN_BS, 0, s>>>(in, n, sums);
-    k_scan_blocks<<<1, 1024, 0, s>>>(sums, nb);
-    k_scan_apply<<<nb, SCAN_BS, 0, s>>>(in, out, n, sums);
+    DR_LAUNCH("k_scan_reduce", (k_scan_reduce), nb, SCAN_BS, 0, s, in, n, sums);
+    DR_LAUNCH("k_scan_blocks", (k_scan_blocks), 1, 1024, 0, s, sums, nb);
+    DR_LAUNCH("k_scan_apply", (k_scan_apply), nb, SCAN_BS, 0, s, in, out, n, sums);
 }
 
 // ---------------------------------------------------------------------------
@@ -194,10 +194,10 @@ void dressi_build_adjacency(const int32_t *tris, int T, int V, void *scratch, Ad
     int64_t n3 = 3 * (int64_t)T;
     dressi_fill_i32(counts, 0, V, s);
     dressi_fill_i32(cursor, 0, V, s);
-    if (n3 > 0) k_count_corners<<<(int)((n3 + 255) / 256), 256, 0, s>>>(tris, n3, V, counts);
+    if (n3 > 0) DR_LAUNCH("k_count_corners", (k_count_corners), (int)((n3 + 255) / 256), 256, 0, s, tris, n3, V, counts);
     dressi_exclusive_scan(counts, adj.offsets, V, tmp, s);
     if (n3 > 0)
-        k_place_corners<<<(int)((n3 + 255) / 256), 256, 0, s>>>(tris, n3, V, adj.offsets, cursor,
+        DR_LAUNCH("k_place_corners", (k_place_corners), (int)((n3 + 255) / 256), 256, 0, s, tris, n3, V, adj.offsets, cursor,
                                                                adj.corners);
-    if (V > 0) k_sort_corners<<<(V + 255) / 256, 256, 0, s>>>(adj.offsets, adj.corners, V);
+    if (V > 0) DR_LAUNCH("k_sort_corners", (k_sort_corners), (V + 255) / 256, 256, 0, s, adj.offsets, adj.corners, V);
 }

@@ -202,10 +202,10 @@ static void launch_raster_k(bool soft, dim3 g, hipStream_t st, const TriSetup *s
                             int W, int ntx, int nt, float r, int32_t *tid, float2 *bary,
                             float *dist) {
     if (soft)
-        k_raster<K, true><<<g, DRESSI_TILE_PIX, 0, st>>>(setup, off, bins, cap, T, H, W, ntx, nt, r,
+        DR_LAUNCH("k_raster", (k_raster<K, true>), g, DRESSI_TILE_PIX, 0, st, setup, off, bins, cap, T, H, W, ntx, nt, r,
                                                          tid, bary, dist);
     else
-        k_raster<K, false><<<g, DRESSI_TILE_PIX, 0, st>>>(setup, off, bins, cap, T, H, W, ntx, nt,
+        DR_LAUNCH("k_raster", (k_raster<K, false>), g, DRESSI_TILE_PIX, 0, st, setup, off, bins, cap, T, H, W, ntx, nt,
                                                           r, tid, bary, dist);
 }
 
@@ -273,11 +273,11 @@ extern "C" int dressi_rasterize(dressi_ctx *ctx, const float *pos_clip, const in
     dressi_fill_i32(counts, 0, (int64_t)B * nt, st);
     dressi_fill_i32(cursor, 0, (int64_t)B * nt, st);
     if (ntri > 0)
-        k_setup_count<<<(int)((ntri + 255) / 256), 256, 0, st>>>(
+        DR_LAUNCH("k_setup_count", (k_setup_count), (int)((ntri + 255) / 256), 256, 0, st, 
             reinterpret_cast<const float4 *>(pos_clip), tris, B, V, T, H, W, cull, margin, ntx, nt,
             setup, counts);
     dressi_exclusive_scan(counts, offs, (int64_t)B * nt, at<void>(S, o[4]), st);
-    k_fill_bins<<<(int)((ntri + 255) / 256 + 1), 256, 0, st>>>(
+    DR_LAUNCH("k_fill_bins", (k_fill_bins), (int)((ntri + 255) / 256 + 1), 256, 0, st, 
         setup, B, T, ntx, nt, offs, cursor, bins, cap,
         reinterpret_cast<unsigned long long *>(ctx->status));
     dim3 g((unsigned)(B * nt));
@@ -421,7 +421,7 @@ void dressi_build_fraglists(const int32_t *tri_id, int B, int K, int H, int W, v
     int np = 256;
     while (np < DRESSI_TILE_PIX * K) np <<= 1;
     if (B * nt > 0)
-        k_fragsort<<<B * nt, DRESSI_TILE_PIX, 0, s>>>(tri_id, K, H, W, ntx, nt, np, fl.n_frag,
+        DR_LAUNCH("k_fragsort", (k_fragsort), B * nt, DRESSI_TILE_PIX, 0, s, tri_id, K, H, W, ntx, nt, np, fl.n_frag,
                                                        fl.n_rec, fl.frag, fl.rec_tri, fl.rec_start);
 }
 
@@ -494,10 +494,10 @@ void dressi_build_tritiles(const FragLists &fl, int B, int T, int K, int H, int 
     void *tmp = at<void>(scratch, c.take(dressi_scan_tmp_bytes(n)));
     dressi_fill_i32(counts, 0, n, s);
     dressi_fill_i32(cursor, 0, n, s);
-    if (B * nt > 0) k_tt_count<<<B * nt, 256, 0, s>>>(fl, K, T, nt, counts);
+    if (B * nt > 0) DR_LAUNCH("k_tt_count", (k_tt_count), B * nt, 256, 0, s, fl, K, T, nt, counts);
     dressi_exclusive_scan(counts, tt.offsets, n, tmp, s);
-    if (B * nt > 0) k_tt_fill<<<B * nt, 256, 0, s>>>(fl, K, T, nt, tt.offsets, cursor, tt.entries);
-    if (n > 0) k_tt_sort<<<(int)((n + 255) / 256), 256, 0, s>>>(tt.offsets, tt.entries, n);
+    if (B * nt > 0) DR_LAUNCH("k_tt_fill", (k_tt_fill), B * nt, 256, 0, s, fl, K, T, nt, tt.offsets, cursor, tt.entries);
+    if (n > 0) DR_LAUNCH("k_tt_sort", (k_tt_sort), (int)((n + 255) / 256), 256, 0, s, tt.offsets, tt.entries, n);
 }
 
 // binary search of triangle t among the sorted records of one tile; returns
@@ -693,11 +693,11 @@ extern "C" int dressi_rasterize_bwd(dressi_ctx *ctx, const float *pos_clip, cons
     float *cg = at<float>(S, o_cg);
     int64_t ntri = (int64_t)B * T;
     if (ntri > 0)
-        k_rast_bwd_tri<<<(int)((ntri + 127) / 128), 128, 0, st>>>(
+        DR_LAUNCH("k_rast_bwd_tri", (k_rast_bwd_tri), (int)((ntri + 127) / 128), 128, 0, st, 
             reinterpret_cast<const float4 *>(pos_clip), tris, B, V, T, H, W, K, cull, margin, ntx,
             nt, fl, reinterpret_cast<const float2 *>(grad_bary), grad_dist, cg);
     int64_t nv = (int64_t)B * V;
-    k_vertex_gather_pos<<<(int)((nv + 255) / 256), 256, 0, st>>>(
+    DR_LAUNCH("k_vertex_gather_pos", (k_vertex_gather_pos), (int)((nv + 255) / 256), 256, 0, st, 
         cg, adj, B, V, T, reinterpret_cast<float4 *>(grad_pos_clip));
     return dressi_launch_check(ctx, "rasterize_bwd");
 }

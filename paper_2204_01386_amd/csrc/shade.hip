@@ -1,0 +1,503 @@
+// Vertex transform, per-vertex attribute assembly (vertex normals), deferred
+// shading and the L2 image loss, forward and backward, for gfx950.
+//
+// All of these are memory-bound elementwise or gather kernels.  Per-vertex
+// sums over incident faces go through the vertex->corner adjacency in
+// ascending corner order, and the loss is reduced in a fixed tree order, so
+// every result is bitwise reproducible.
+#include "dressi_internal.h"
+
+// ---------------------------------------------------------------------------
+// transform
+// ---------------------------------------------------------------------------
+__global__ void k_transform(const float *__restrict__ pos, const float *__restrict__ mvp, int B, int V,
+                            float4 *__restrict__ out) {
+    int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= (int64_t)B * V) return;
+    int b = (int)(gid / V), v = (int)(gid - (int64_t)b * V);
+    const float *M = mvp + 16 * b;
+    float x = pos[3 * (int64_t)v], y = pos[3 * (int64_t)v + 1], z = pos[3 * (int64_t)v + 2];
+    float4 o;
+    o.x = M[0] * x + M[1] * y + M[2] * z + M[3];
+    o.y = M[4] * x + M[5] * y + M[6] * z + M[7];
+    o.z = M[8] * x + M[9] * y + M[10] * z + M[11];
+    o.w = M[12] * x + M[13] * y + M[14] * z + M[15];
+    out[gid] = o;
+}
+
+__global__ void k_transform_bwd(const float *__restrict__ mvp, int B, int V,
+                                const float4 *__restrict__ g, float *__restrict__ grad_pos) {
+    int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= V) return;
+    float gx = 0.0f, gy = 0.0f, gz = 0.0f;
+    for (int b = 0; b < B; b++) {
+        const float *M = mvp + 16 * b;
+        float4 q = g[(int64_t)b * V + v];
+        gx += M[0] * q.x + M[4] * q.y + M[8] * q.z + M[12] * q.w;
+        gy += M[1] * q.x + M[5] * q.y + M[9] * q.z + M[13] * q.w;
+        gz += M[2] * q.x + M[6] * q.y + M[10] * q.z + M[14] * q.w;
+    }
+    grad_pos[3 * (int64_t)v] = gx;
+    grad_pos[3 * (int64_t)v + 1] = gy;
+    grad_pos[3 * (int64_t)v + 2] = gz;
+}
+
+extern "C" int dressi_transform(dressi_ctx *ctx, const float *pos, const float *mvp, int B, int V,
+                                float *pos_clip, void *stream) {
+    if (!ctx) return DRESSI_EINVAL;
+    if (B < 0 || V < 0) return dressi_fail(ctx, DRESSI_EINVAL, "transform: bad dimensions");
+    if ((int64_t)B * V == 0) return DRESSI_OK;
+    if (!pos || !mvp || !pos_clip) return dressi_fail(ctx, DRESSI_EINVAL, "transform: null pointer");
+    int64_t n = (int64_t)B * V;
+    DR_LAUNCH("k_transform", (k_transform), (int)((n + 255) / 256), 256, 0, (hipStream_t)stream, 
+        pos, mvp, B, V, reinterpret_cast<float4 *>(pos_clip));
+    return dressi_launch_check(ctx, "transform");
+}
+
+extern "C" int dressi_transform_bwd(dressi_ctx *ctx, const float *mvp, int B, int V,
+                                    const float *grad_clip, float *grad_pos, void *stream) {
+    if (!ctx) return DRESSI_EINVAL;
+    if (B < 0 || V < 0) return dressi_fail(ctx, DRESSI_EINVAL, "transform_bwd: bad dimensions");
+    if (V == 0) return DRESSI_OK;
+    if (!grad_pos || (B > 0 && (!mvp || !grad_clip)))
+        return dressi_fail(ctx, DRESSI_EINVAL, "transform_bwd: null pointer");
+    DR_LAUNCH("k_transform_bwd", (k_transform_bwd), (V + 255) / 256, 256, 0, (hipStream_t)stream, 
+        mvp, B, V, reinterpret_cast<const float4 *>(grad_clip), grad_pos);
+    return dressi_launch_check(ctx, "transform_bwd");
+}
+
+// ---------------------------------------------------------------------------
+// per-vertex attributes: (normal, position[, tangent])
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float3 ld3(const float *p) { return make_float3(p[0], p[1], p[2]); }
+__device__ __forceinline__ float3 operator+(float3 a, float3 b) { return make_float3(a.x + b.x, a.y + b.y, a.z + b.z); }
+__device__ __forceinline__ float3 operator-(float3 a, float3 b) { return make_float3(a.x - b.x, a.y - b.y, a.z - b.z); }
+__device__ __forceinline__ float3 operator*(float s, float3 a) { return make_float3(s * a.x, s * a.y, s * a.z); }
+__device__ __forceinline__ float dot3(float3 a, float3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ float3 cross3(float3 a, float3 b) {
+    return make_float3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+__device__ __forceinline__ float3 normalize3(float3 a) {
+    float l = sqrtf(dot3(a, a));
+    return l > 0.0f ? (1.0f / l) * a : make_float3(0.0f, 0.0f, 0.0f);
+}
+// gradient of normalize(a): (g - (g.n) n) / |a|
+__device__ __forceinline__ float3 normalize3_bwd(float3 a, float3 g) {
+    float l = sqrtf(dot3(a, a));
+    if (!(l > 0.0f)) return make_float3(0.0f, 0.0f, 0.0f);
+    float3 n = (1.0f / l) * a;
+    return (1.0f / l) * (g - dot3(g, n) * n);
+}
+
+__global__ void k_face_normals(const float *__restrict__ pos, const int32_t *__restrict__ tris, int T,
+                               int V, float *__restrict__ fn) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= T) return;
+    int a = tris[3 * t], b = tris[3 * t + 1], c = tris[3 * t + 2];
+    float3 n = make_float3(0.0f, 0.0f, 0.0f);
+    if (a >= 0 && a < V && b >= 0 && b < V && c >= 0 && c < V) {
+        float3 p0 = ld3(pos + 3 * (int64_t)a);
+        n = cross3(ld3(pos + 3 * (int64_t)b) - p0, ld3(pos + 3 * (int64_t)c) - p0);
+    }
+    fn[3 * (int64_t)t] = n.x;
+    fn[3 * (int64_t)t + 1] = n.y;
+    fn[3 * (int64_t)t + 2] = n.z;
+}
+
+__device__ __forceinline__ float3 vertex_acc(const float *fn, const Adjacency &adj, int v) {
+    float3 s = make_float3(0.0f, 0.0f, 0.0f);
+    for (int j = adj.offsets[v]; j < adj.offsets[v + 1]; j++) s = s + ld3(fn + 3 * (int64_t)(adj.corners[j] / 3));
+    return s;
+}
+
+__global__ void k_vertex_attrs(const float *__restrict__ pos, const float *__restrict__ extra,
+                               const float *__restrict__ fn, Adjacency adj, int V, int C,
+                               float *__restrict__ out) {
+    int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= V) return;
+    float3 n = normalize3(vertex_acc(fn, adj, v));
+    float *o = out + (int64_t)v * C;
+    o[0] = n.x; o[1] = n.y; o[2] = n.z;
+    o[3] = pos[3 * (int64_t)v]; o[4] = pos[3 * (int64_t)v + 1]; o[5] = pos[3 * (int64_t)v + 2];
+    if (C == 9) {
+        o[6] = extra[3 * (int64_t)v]; o[7] = extra[3 * (int64_t)v + 1]; o[8] = extra[3 * (int64_t)v + 2];
+    }
+}
+
+__global__ void k_vertex_attrs_bwd1(const float *__restrict__ fn, Adjacency adj, int V, int C,
+                                    const float *__restrict__ g, float *__restrict__ gacc) {
+    int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= V) return;
+    float3 a = vertex_acc(fn, adj, v);
+    float3 r = normalize3_bwd(a, ld3(g + (int64_t)v * C));
+    gacc[3 * (int64_t)v] = r.x;
+    gacc[3 * (int64_t)v + 1] = r.y;
+    gacc[3 * (int64_t)v + 2] = r.z;
+}
+
+// per face: n = e1 x e2 -> corner gradients (c0: -(g1+g2), c1: g1, c2: g2)
+__global__ void k_vertex_attrs_bwd2(const float *__restrict__ pos, const int32_t *__restrict__ tris,
+                                    int T, int V, const float *__restrict__ gacc,
+                                    float *__restrict__ cg) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= T) return;
+    int a = tris[3 * t], b = tris[3 * t + 1], c = tris[3 * t + 2];
+    float3 g1 = make_float3(0.0f, 0.0f, 0.0f), g2 = g1;
+    if (a >= 0 && a < V && b >= 0 && b < V && c >= 0 && c < V) {
+        float3 gn = ld3(gacc + 3 * (int64_t)a) + ld3(gacc + 3 * (int64_t)b) + ld3(gacc + 3 * (int64_t)c);
+        float3 p0 = ld3(pos + 3 * (int64_t)a);
+        float3 e1 = ld3(pos + 3 * (int64_t)b) - p0, e2 = ld3(pos + 3 * (int64_t)c) - p0;
+        g1 = cross3(e2, gn);
+        g2 = cross3(gn, e1);
+    }
+    float3 g0 = make_float3(-(g1.x + g2.x), -(g1.y + g2.y), -(g1.z + g2.z));
+    float *o = cg + 9 * (int64_t)t;
+    o[0] = g0.x; o[1] = g0.y; o[2] = g0.z;
+    o[3] = g1.x; o[4] = g1.y; o[5] = g1.z;
+    o[6] = g2.x; o[7] = g2.y; o[8] = g2.z;
+}
+
+__global__ void k_vertex_attrs_bwd3(const float *__restrict__ cg, Adjacency adj, int V, int C,
+                                    const float *__restrict__ g, const float *__restrict__ gin,
+                                    float *__restrict__ grad_pos) {
+    int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= V) return;
+    float3 s = ld3(g + (int64_t)v * C + 3);
+    if (gin) s = s + ld3(gin + 3 * (int64_t)v);
+    for (int j = adj.offsets[v]; j < adj.offsets[v + 1]; j++) s = s + ld3(cg + 3 * (int64_t)adj.corners[j]);
+    grad_pos[3 * (int64_t)v] = s.x;
+    grad_pos[3 * (int64_t)v + 1] = s.y;
+    grad_pos[3 * (int64_t)v + 2] = s.z;
+}
+
+extern "C" int dressi_vertex_attrs(dressi_ctx *ctx, const float *pos, const int32_t *tris, int V, int T,
+                                   const float *extra, float *out, void *stream) {
+    if (!ctx) return DRESSI_EINVAL;
+    if (V < 0 || T < 0) return dressi_fail(ctx, DRESSI_EINVAL, "vertex_attrs: bad dimensions");
+    if (V == 0) return DRESSI_OK;
+    if (!pos || !out || (T > 0 && !tris)) return dressi_fail(ctx, DRESSI_EINVAL, "vertex_attrs: null pointer");
+    hipStream_t st = (hipStream_t)stream;
+    Carver c;
+    size_t o_adj = c.take(dressi_adjacency_bytes(V, T));
+    size_t o_fn = c.take(sizeof(float) * 3 * (size_t)(T > 0 ? T : 1));
+    int rc = dressi_scratch(ctx, c.off, st);
+    if (rc) return rc;
+    Adjacency adj;
+    dressi_build_adjacency(tris, T, V, at<void>(ctx->scratch, o_adj), adj, st);
+    float *fn = at<float>(ctx->scratch, o_fn);
+    if (T > 0) DR_LAUNCH("k_face_normals", (k_face_normals), (T + 255) / 256, 256, 0, st, pos, tris, T, V, fn);
+    int C = extra ? 9 : 6;
+    DR_LAUNCH("k_vertex_attrs", (k_vertex_attrs), (V + 255) / 256, 256, 0, st, pos, extra, fn, adj, V, C, out);
+    return dressi_launch_check(ctx, "vertex_attrs");
+}
+
+extern "C" int dressi_vertex_attrs_bwd(dressi_ctx *ctx, const float *pos, const int32_t *tris, int V,
+                                       int T, int C, const float *grad_out,
+                                       const float *grad_pos_in, float *grad_pos, void *stream) {
+    if (!ctx) return DRESSI_EINVAL;
+    if (V < 0 || T < 0 || (C != 6 && C != 9))
+        return dressi_fail(ctx, DRESSI_EINVAL, "vertex_attrs_bwd: bad dimensions (C must be 6 or 9)");
+    if (V == 0) return DRESSI_OK;
+    if (!pos || !grad_out || !grad_pos || (T > 0 && !tris))
+        return dressi_fail(ctx, DRESSI_EINVAL, "vertex_attrs_bwd: null pointer");
+    hipStream_t st = (hipStream_t)stream;
+    Carver c;
+    size_t o_adj = c.take(dressi_adjacency_bytes(V, T));
+    size_t o_fn = c.take(sizeof(float) * 3 * (size_t)(T > 0 ? T : 1));
+    size_t o_ga = c.take(sizeof(float) * 3 * (size_t)V);
+    size_t o_cg = c.take(sizeof(float) * 9 * (size_t)(T > 0 ? T : 1));
+    int rc = dressi_scratch(ctx, c.off, st);
+    if (rc) return rc;
+    void *S = ctx->scratch;
+    Adjacency adj;
+    dressi_build_adjacency(tris, T, V, at<void>(S, o_adj), adj, st);
+    float *fn = at<float>(S, o_fn), *ga = at<float>(S, o_ga), *cg = at<float>(S, o_cg);
+    if (T > 0) DR_LAUNCH("k_face_normals", (k_face_normals), (T + 255) / 256, 256, 0, st, pos, tris, T, V, fn);
+    DR_LAUNCH("k_vertex_attrs_bwd1", (k_vertex_attrs_bwd1), (V + 255) / 256, 256, 0, st, fn, adj, V, C, grad_out, ga);
+    if (T > 0) DR_LAUNCH("k_vertex_attrs_bwd2", (k_vertex_attrs_bwd2), (T + 255) / 256, 256, 0, st, pos, tris, T, V, ga, cg);
+    DR_LAUNCH("k_vertex_attrs_bwd3", (k_vertex_attrs_bwd3), (V + 255) / 256, 256, 0, st, cg, adj, V, C, grad_out, grad_pos_in,
+                                                         grad_pos);
+    return dressi_launch_check(ctx, "vertex_attrs_bwd");
+}
+
+// ---------------------------------------------------------------------------
+// deferred shading
+// ---------------------------------------------------------------------------
+__constant__ float c_light[3] = {0.408248290463863f, 0.408248290463863f, 0.816496580927726f};
+
+struct ShadeState {
+    float3 nin, nh, t, tp, th, bh, m, u, np;   // normal-map chain (np = shading normal)
+    float3 vv, vh;                              // view vector and its direction
+    float ndl, rv, spec, base, kd;
+    float3 r;
+    float a[4];
+    float3 e;
+};
+
+__device__ __forceinline__ void shade_forward(int mode, const dressi_frag_in &in, const float *eye,
+                                              int64_t i, bool need_view, ShadeState &s) {
+    s.nin = ld3(in.normal + i * in.normal_stride);
+    s.nh = normalize3(s.nin);
+    s.np = s.nh;
+    if (in.tangent && in.nmap) {
+        s.t = ld3(in.tangent + i * in.tangent_stride);
+        s.m = ld3(in.nmap + i * in.nmap_stride);
+        s.tp = s.t - dot3(s.t, s.nh) * s.nh;
+        s.th = normalize3(s.tp);
+        s.bh = cross3(s.nh, s.th);
+        s.u = s.m.x * s.th + s.m.y * s.bh + s.m.z * s.nh;
+        s.np = normalize3(s.u);
+    }
+    if (need_view) {
+        s.vv = ld3(eye) - ld3(in.pos + i * in.pos_stride);
+        s.vh = normalize3(s.vv);
+    }
+    const float3 L = make_float3(c_light[0], c_light[1], c_light[2]);
+    s.ndl = dot3(s.np, L);
+    s.kd = mode == DRESSI_SHADE_LAMBERT ? 0.9f : 0.8f;
+    s.base = 0.1f + s.kd * fmaxf(s.ndl, 0.0f);
+    s.spec = 0.0f;
+    s.rv = 0.0f;
+    if (mode != DRESSI_SHADE_LAMBERT) {
+        s.r = (2.0f * s.ndl) * s.np - L;
+        s.rv = dot3(s.r, s.vh);
+        if (s.rv > 0.0f) {
+            float r2 = s.rv * s.rv, r4 = r2 * r2, r8 = r4 * r4, r16 = r8 * r8;
+            s.spec = r16 * r16;
+        }
+    }
+    const float *ap = in.albedo + i * in.albedo_stride;
+    s.a[0] = ap[0]; s.a[1] = ap[1]; s.a[2] = ap[2];
+    s.a[3] = in.albedo_channels > 3 ? ap[3] : 0.0f;
+    s.e = make_float3(0.0f, 0.0f, 0.0f);
+    if (mode == DRESSI_SHADE_PHONG_ENV && in.env) s.e = ld3(in.env + i * in.env_stride);
+}
+
+__global__ void k_shade(int mode, dressi_frag_in in, const float *__restrict__ eye,
+                        const int32_t *__restrict__ tri_id, int64_t N, int64_t Npv,
+                        float *__restrict__ color, float *__restrict__ dir) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    if (tri_id[i] < 0) {
+        if (color) { color[3 * i] = 0.0f; color[3 * i + 1] = 0.0f; color[3 * i + 2] = 0.0f; }
+        if (dir) { dir[3 * i] = 0.0f; dir[3 * i + 1] = 0.0f; dir[3 * i + 2] = 0.0f; }
+        return;
+    }
+    int b = (int)(i / Npv);
+    ShadeState s;
+    shade_forward(mode, in, eye + 3 * b, i, mode != DRESSI_SHADE_LAMBERT || dir != nullptr, s);
+    if (dir) {
+        float3 d = (2.0f * dot3(s.np, s.vh)) * s.np - s.vh;
+        dir[3 * i] = d.x; dir[3 * i + 1] = d.y; dir[3 * i + 2] = d.z;
+    }
+    if (color) {
+        float add = 0.0f;
+        if (mode != DRESSI_SHADE_LAMBERT) add = 0.2f * s.a[3] * s.spec;
+        float env = mode == DRESSI_SHADE_PHONG_ENV ? 0.5f * s.a[3] : 0.0f;
+        color[3 * i] = s.a[0] * s.base + add + env * s.e.x;
+        color[3 * i + 1] = s.a[1] * s.base + add + env * s.e.y;
+        color[3 * i + 2] = s.a[2] * s.base + add + env * s.e.z;
+    }
+}
+
+__device__ __forceinline__ void st3(float *p, int64_t i, int stride, float3 v) {
+    float *q = p + i * stride;
+    q[0] = v.x; q[1] = v.y; q[2] = v.z;
+}
+
+__global__ void k_shade_bwd(int mode, dressi_frag_in in, const float *__restrict__ eye,
+                            const int32_t *__restrict__ tri_id, int64_t N, int64_t Npv,
+                            const float *__restrict__ grad_color, const float *__restrict__ grad_dir,
+                            dressi_frag_grad gr) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const float3 Z = make_float3(0.0f, 0.0f, 0.0f);
+    if (tri_id[i] < 0) {
+        if (gr.normal) st3(gr.normal, i, gr.normal_stride, Z);
+        if (gr.pos) st3(gr.pos, i, gr.pos_stride, Z);
+        if (gr.tangent) st3(gr.tangent, i, gr.tangent_stride, Z);
+        if (gr.nmap) st3(gr.nmap, i, gr.nmap_stride, Z);
+        if (gr.env) st3(gr.env, i, gr.env_stride, Z);
+        if (gr.albedo) {
+            float *q = gr.albedo + i * gr.albedo_stride;
+            for (int c = 0; c < in.albedo_channels; c++) q[c] = 0.0f;
+        }
+        return;
+    }
+    int b = (int)(i / Npv);
+    bool need_geo = gr.normal || gr.pos || gr.tangent || gr.nmap;
+    ShadeState s;
+    shade_forward(mode, in, eye + 3 * b, i, mode != DRESSI_SHADE_LAMBERT || grad_dir != nullptr, s);
+    float3 g = grad_color ? ld3(grad_color + 3 * i) : Z;
+    float gsum = g.x + g.y + g.z;
+    if (gr.albedo) {
+        float *q = gr.albedo + i * gr.albedo_stride;
+        q[0] = g.x * s.base; q[1] = g.y * s.base; q[2] = g.z * s.base;
+        if (in.albedo_channels > 3) {
+            float ga = 0.0f;
+            if (mode != DRESSI_SHADE_LAMBERT) ga += 0.2f * s.spec * gsum;
+            if (mode == DRESSI_SHADE_PHONG_ENV) ga += 0.5f * dot3(g, s.e);
+            q[3] = ga;
+        }
+    }
+    if (gr.env) st3(gr.env, i, gr.env_stride, mode == DRESSI_SHADE_PHONG_ENV ? (0.5f * s.a[3]) * g : Z);
+    if (!need_geo) return;
+    const float3 L = make_float3(c_light[0], c_light[1], c_light[2]);
+    float3 gnp = Z, gvh = Z;
+    float gdot = g.x * s.a[0] + g.y * s.a[1] + g.z * s.a[2];
+    if (s.ndl > 0.0f) gnp = (s.kd * gdot) * L;
+    if (mode != DRESSI_SHADE_LAMBERT && s.rv > 0.0f) {
+        float r2 = s.rv * s.rv, r4 = r2 * r2, r8 = r4 * r4, r16 = r8 * r8;
+        float r31 = r16 * r8 * r4 * r2 * s.rv;
+        float grv = 0.2f * s.a[3] * gsum * 32.0f * r31;
+        float3 gr_ = grv * s.vh;
+        gvh = gvh + grv * s.r;
+        gnp = gnp + (2.0f * s.ndl) * gr_ + (2.0f * dot3(gr_, s.np)) * L;
+    }
+    if (grad_dir) {
+        float3 gd = ld3(grad_dir + 3 * i);
+        float d = dot3(s.np, s.vh), gdn = dot3(gd, s.np);
+        gnp = gnp + (2.0f * d) * gd + (2.0f * gdn) * s.vh;
+        gvh = gvh + (2.0f * gdn) * s.np - gd;
+    }
+    if (gr.pos) {
+        float3 gvv = (mode != DRESSI_SHADE_LAMBERT || grad_dir) ? normalize3_bwd(s.vv, gvh) : Z;
+        st3(gr.pos, i, gr.pos_stride, make_float3(-gvv.x, -gvv.y, -gvv.z));
+    }
+    if (in.tangent && in.nmap) {
+        float3 gu = normalize3_bwd(s.u, gnp);
+        if (gr.nmap) st3(gr.nmap, i, gr.nmap_stride, make_float3(dot3(gu, s.th), dot3(gu, s.bh), dot3(gu, s.nh)));
+        float3 gth = s.m.x * gu, gbh = s.m.y * gu, gnh = s.m.z * gu;
+        gnh = gnh + cross3(s.th, gbh);
+        gth = gth + cross3(gbh, s.nh);
+        float3 gtp = normalize3_bwd(s.tp, gth);
+        float d = dot3(s.t, s.nh);
+        float gd = -dot3(gtp, s.nh);
+        if (gr.tangent) st3(gr.tangent, i, gr.tangent_stride, gtp + gd * s.nh);
+        gnh = gnh + (-d) * gtp + gd * s.t;
+        if (gr.normal) st3(gr.normal, i, gr.normal_stride, normalize3_bwd(s.nin, gnh));
+    } else {
+        if (gr.normal) st3(gr.normal, i, gr.normal_stride, normalize3_bwd(s.nin, gnp));
+        if (gr.tangent) st3(gr.tangent, i, gr.tangent_stride, Z);
+        if (gr.nmap) st3(gr.nmap, i, gr.nmap_stride, Z);
+    }
+}
+
+static int check_shade(dressi_ctx *ctx, int mode, const dressi_frag_in *in, const float *eye,
+                       const int32_t *tri_id, int B, int64_t Npv) {
+    if (!ctx) return DRESSI_EINVAL;
+    if (mode < DRESSI_SHADE_LAMBERT || mode > DRESSI_SHADE_PHONG_ENV)
+        return dressi_fail(ctx, DRESSI_EINVAL, "shade: bad mode");
+    if (!in || B < 0 || Npv < 0) return dressi_fail(ctx, DRESSI_EINVAL, "shade: bad arguments");
+    if ((int64_t)B * Npv == 0) return DRESSI_OK;
+    if (!in->normal || !in->albedo || !eye || !tri_id)
+        return dressi_fail(ctx, DRESSI_EINVAL, "shade: normal, albedo, eye and tri_id are required");
+    if (in->albedo_channels != 3 && in->albedo_channels != 4)
+        return dressi_fail(ctx, DRESSI_EINVAL, "shade: albedo_channels must be 3 or 4");
+    if (mode != DRESSI_SHADE_LAMBERT && (!in->pos || in->albedo_channels != 4))
+        return dressi_fail(ctx, DRESSI_EINVAL, "shade: Phong modes need pos and rgba albedo");
+    if ((in->tangent == nullptr) != (in->nmap == nullptr))
+        return dressi_fail(ctx, DRESSI_EINVAL, "shade: tangent and nmap go together");
+    return DRESSI_OK;
+}
+
+extern "C" int dressi_shade(dressi_ctx *ctx, int mode, const dressi_frag_in *in, const float *eye,
+                            const int32_t *tri_id, int B, int64_t Npv, float *color, float *dir,
+                            void *stream) {
+    int rc = check_shade(ctx, mode, in, eye, tri_id, B, Npv);
+    if (rc) return rc;
+    int64_t N = (int64_t)B * Npv;
+    if (N == 0) return DRESSI_OK;
+    if (dir && !in->pos) return dressi_fail(ctx, DRESSI_EINVAL, "shade: dir needs pos");
+    if (color && mode == DRESSI_SHADE_PHONG_ENV && !in->env)
+        return dressi_fail(ctx, DRESSI_EINVAL, "shade: PHONG_ENV colour needs the environment sample");
+    DR_LAUNCH("k_shade", (k_shade), (int)((N + 255) / 256), 256, 0, (hipStream_t)stream, mode, *in, eye, tri_id, N, Npv,
+                                                                      color, dir);
+    return dressi_launch_check(ctx, "shade");
+}
+
+extern "C" int dressi_shade_bwd(dressi_ctx *ctx, int mode, const dressi_frag_in *in, const float *eye,
+                                const int32_t *tri_id, int B, int64_t Npv, const float *grad_color,
+                                const float *grad_dir, const dressi_frag_grad *grad, void *stream) {
+    int rc = check_shade(ctx, mode, in, eye, tri_id, B, Npv);
+    if (rc) return rc;
+    if (!grad) return dressi_fail(ctx, DRESSI_EINVAL, "shade_bwd: null grad");
+    int64_t N = (int64_t)B * Npv;
+    if (N == 0) return DRESSI_OK;
+    if (grad_dir && !in->pos) return dressi_fail(ctx, DRESSI_EINVAL, "shade_bwd: grad_dir needs pos");
+    if (mode == DRESSI_SHADE_PHONG_ENV && !in->env && (grad->albedo || grad->normal || grad->pos))
+        return dressi_fail(ctx, DRESSI_EINVAL, "shade_bwd: PHONG_ENV needs the environment sample");
+    DR_LAUNCH("k_shade_bwd", (k_shade_bwd), (int)((N + 255) / 256), 256, 0, (hipStream_t)stream, mode, *in, eye, tri_id, N, Npv,
+                                                                          grad_color, grad_dir, *grad);
+    return dressi_launch_check(ctx, "shade_bwd");
+}
+
+// ---------------------------------------------------------------------------
+// L2 loss with a fixed-order reduction
+// ---------------------------------------------------------------------------
+#define LOSS_BS 256
+#define LOSS_MAX_BLOCKS 1024
+
+__global__ void __launch_bounds__(LOSS_BS)
+    k_loss_l2(const float *__restrict__ color, const float *__restrict__ sil,
+              const float *__restrict__ target, int64_t n, float inv, float *__restrict__ grad_color,
+              float *__restrict__ grad_sil, float *__restrict__ partial) {
+    __shared__ float red[LOSS_BS];
+    float acc = 0.0f;
+    for (int64_t i = (int64_t)blockIdx.x * LOSS_BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * LOSS_BS) {
+        float4 t = reinterpret_cast<const float4 *>(target)[i];
+        float d0 = color[3 * i] - t.x, d1 = color[3 * i + 1] - t.y, d2 = color[3 * i + 2] - t.z;
+        float d3 = sil[i] - t.w;
+        acc += d0 * d0 + d1 * d1 + d2 * d2 + d3 * d3;
+        if (grad_color) {
+            grad_color[3 * i] = 2.0f * inv * d0;
+            grad_color[3 * i + 1] = 2.0f * inv * d1;
+            grad_color[3 * i + 2] = 2.0f * inv * d2;
+        }
+        if (grad_sil) grad_sil[i] = 2.0f * inv * d3;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = LOSS_BS / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(LOSS_BS) k_loss_final(const float *__restrict__ partial, int nb, float inv,
+                                                        float *__restrict__ loss) {
+    __shared__ float red[LOSS_BS];
+    float acc = 0.0f;
+    for (int i = threadIdx.x; i < nb; i += LOSS_BS) acc += partial[i];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = LOSS_BS / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) loss[0] = red[0] * inv;
+}
+
+extern "C" int dressi_loss_l2(dressi_ctx *ctx, const float *color, const float *sil, const float *target,
+                              int B, int H, int W, float *loss, float *grad_color, float *grad_sil,
+                              void *stream) {
+    if (!ctx) return DRESSI_EINVAL;
+    if (B < 0 || H < 0 || W < 0) return dressi_fail(ctx, DRESSI_EINVAL, "loss_l2: bad dimensions");
+    int64_t n = (int64_t)B * H * W;
+    if (!loss) return dressi_fail(ctx, DRESSI_EINVAL, "loss_l2: null loss");
+    if (n > 0 && (!color || !sil || !target)) return dressi_fail(ctx, DRESSI_EINVAL, "loss_l2: null input");
+    hipStream_t st = (hipStream_t)stream;
+    int nb = (int)((n + LOSS_BS - 1) / LOSS_BS);
+    if (nb > LOSS_MAX_BLOCKS) nb = LOSS_MAX_BLOCKS;
+    if (nb < 1) nb = 1;
+    Carver c;
+    size_t o_p = c.take(sizeof(float) * nb);
+    int rc = dressi_scratch(ctx, c.off, st);
+    if (rc) return rc;
+    float *partial = at<float>(ctx->scratch, o_p);
+    float inv = n > 0 ? 1.0f / (4.0f * (float)n) : 0.0f;
+    DR_LAUNCH("k_loss_l2", (k_loss_l2), nb, LOSS_BS, 0, st, color, sil, target, n, inv, grad_color, grad_sil, partial);
+    DR_LAUNCH("k_loss_final", (k_loss_final), 1, LOSS_BS, 0, st, partial, nb, 1.0f / (4.0f * (float)(n > 0 ? n : 1)), loss);
+    return dressi_launch_check(ctx, "loss_l2");
+}

@@ -221,12 +221,12 @@ extern "C" int dressi_softras(dressi_ctx *ctx, const float *color, const float *
         uint8_t *bnd = at<uint8_t>(ctx->scratch, o_b);
         rows = at<uint8_t>(ctx->scratch, o_r);
         int g = (int)((n + 255) / 256);
-        k_boundary<<<g, 256, 0, st>>>(tri_id, dist, B, K, H, W, bnd);
-        k_dilate_rows<<<g, 256, 0, st>>>(bnd, B, H, W, rho, rows);
+        DR_LAUNCH("k_boundary", (k_boundary), g, 256, 0, st, tri_id, dist, B, K, H, W, bnd);
+        DR_LAUNCH("k_dilate_rows", (k_dilate_rows), g, 256, 0, st, bnd, B, H, W, rho, rows);
     }
     float inv_sigma = mode == DRESSI_BLEND_HARD ? 0.0f : 1.0f / sigma;
     int g = (int)((n + 255) / 256);
-    KDISPATCH(K, k_blend<KK><<<g, 256, 0, st>>>(color, dist, tri_id, B, H, W, Cc, inv_sigma, mode,
+    KDISPATCH(K, DR_LAUNCH("k_blend", (k_blend<KK>), g, 256, 0, st, color, dist, tri_id, B, H, W, Cc, inv_sigma, mode,
                                                  rho, rows, out_color, out_sil, edge_mask));
     return dressi_launch_check(ctx, "softras");
 }
@@ -246,7 +246,7 @@ extern "C" int dressi_softras_bwd(dressi_ctx *ctx, const float *color, const flo
     hipStream_t st = (hipStream_t)stream;
     float inv_sigma = sigma > 0.0f ? 1.0f / sigma : 0.0f;
     int g = (int)((n + 255) / 256);
-    KDISPATCH(K, k_blend_bwd<KK><<<g, 256, 0, st>>>(color, dist, tri_id, B, H, W, Cc, inv_sigma,
+    KDISPATCH(K, DR_LAUNCH("k_blend_bwd", (k_blend_bwd<KK>), g, 256, 0, st, color, dist, tri_id, B, H, W, Cc, inv_sigma,
                                                      edge_mask, grad_color, grad_sil,
                                                      grad_layer_color, grad_dist));
     return dressi_launch_check(ctx, "softras_bwd");

@@ -309,7 +309,7 @@ extern "C" int dressi_texture(dressi_ctx *ctx, const float *tex, const dressi_te
     if (n == 0) return DRESSI_OK;
     if (!out) return dressi_fail(ctx, DRESSI_EINVAL, "texture: null out");
     hipStream_t st = (hipStream_t)stream;
-    k_tex_fwd<<<(int)((n + 255) / 256), 256, 0, st>>>(tex, *td, coord, tri_id, n, out);
+    DR_LAUNCH("k_tex_fwd", (k_tex_fwd), (int)((n + 255) / 256), 256, 0, st, tex, *td, coord, tri_id, n, out);
     return dressi_launch_check(ctx, "texture");
 }
 
@@ -328,7 +328,7 @@ extern "C" int dressi_texture_bwd(dressi_ctx *ctx, const float *tex, const dress
         return dressi_fail(ctx, DRESSI_EINVAL, "texture_bwd: repeat wrap needs at least 3 texels");
     hipStream_t st = (hipStream_t)stream;
     if (grad_coord && n > 0)
-        k_tex_bwd_coord<<<(int)((n + 255) / 256), 256, 0, st>>>(tex, *td, coord, tri_id, n, grad_out,
+        DR_LAUNCH("k_tex_bwd_coord", (k_tex_bwd_coord), (int)((n + 255) / 256), 256, 0, st, tex, *td, coord, tri_id, n, grad_out,
                                                                 grad_coord);
     if (grad_tex) {
         int64_t cells = (int64_t)(td->kind == DRESSI_TEX_CUBE ? 6 : 1) * td->Ht * td->Wt;
@@ -339,15 +339,15 @@ extern "C" int dressi_texture_bwd(dressi_ctx *ctx, const float *tex, const dress
         int32_t *inv = at<int32_t>(ctx->scratch, o_inv);
         if (n > 0) {
             dressi_fill_i32(inv, -1, cells * S, st);
-            k_invuv_build<<<(int)((n + 255) / 256), 256, 0, st>>>(*td, coord, tri_id, npix, S, inv);
+            DR_LAUNCH("k_invuv_build", (k_invuv_build), (int)((n + 255) / 256), 256, 0, st, *td, coord, tri_id, npix, S, inv);
         }
         int g = (int)((cells + 255) / 256);
         if (td->Ct == 4)
-            k_invuv_gather<4><<<g, 256, 0, st>>>(*td, coord, npix, S, inv, grad_out, grad_tex);
+            DR_LAUNCH("k_invuv_gather", (k_invuv_gather<4>), g, 256, 0, st, *td, coord, npix, S, inv, grad_out, grad_tex);
         else if (td->Ct == 3)
-            k_invuv_gather<3><<<g, 256, 0, st>>>(*td, coord, npix, S, inv, grad_out, grad_tex);
+            DR_LAUNCH("k_invuv_gather", (k_invuv_gather<3>), g, 256, 0, st, *td, coord, npix, S, inv, grad_out, grad_tex);
         else
-            k_invuv_gather<0><<<g, 256, 0, st>>>(*td, coord, npix, S, inv, grad_out, grad_tex);
+            DR_LAUNCH("k_invuv_gather", (k_invuv_gather<0>), g, 256, 0, st, *td, coord, npix, S, inv, grad_out, grad_tex);
     }
     return dressi_launch_check(ctx, "texture_bwd");
 }

@@ -335,4 +335,12 @@ def config3(seed: int = 0, n_views: int = 16, H: int = 512, subdiv: int = 6,
     s.shading = "phong_env"
     s.nmap = normal_map(tex_size, tex_size, seed + 7)
     s.env = cube_env_map(env_size, seed + 11)
+    s.extra["tangent"] = sphere_tangents(s.pos)
     return s
+
+
+def sphere_tangents(pos: np.ndarray):
+    """Raw per-vertex tangent (-sin phi, 0, cos phi), phi = atan2(z, x): the
+    direction of growing u of the spherical UVs (orthogonalised per pixel)."""
+    phi = np.arctan2(pos[:, 2].astype(np.float64), pos[:, 0].astype(np.float64))
+    return np.stack([-np.sin(phi), np.zeros_like(phi), np.cos(phi)], -1).astype(np.float32)

@@ -1,0 +1,206 @@
+"""GPU parity of the render-step stages (transform, vertex attributes, shading,
+loss) and of the whole forward+backward step against the oracle, plus
+determinism and hipGraph-capture replay."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import step as ostep
+from test_gpu_parity import assert_grad_close, assert_vals_close, dev, host
+from paper_2204_01386_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2204_01386_amd import binding
+    return binding
+
+
+# ---------------------------------------------------------------------------
+# stages
+# ---------------------------------------------------------------------------
+def test_transform(B):
+    s = scenes.config3(n_views=4, subdiv=3, H=64, tex_size=64, env_size=8)
+    pc = B.dressi_transform(dev(s.pos), dev(s.mvp))
+    ref = oracle.transform_f32(s.pos, s.mvp)
+    assert np.array_equal(host(pc), ref), "clip coordinates must match the oracle's float order"
+    g = np.random.default_rng(0).standard_normal(ref.shape).astype(np.float32)
+    gp = B.dressi_transform_bwd(dev(s.mvp), dev(g))
+    assert_grad_close(host(gp), oracle.transform_bwd(s.mvp, g), what="transform_bwd")
+
+
+@pytest.mark.parametrize("extra", [False, True])
+def test_vertex_attrs(B, extra):
+    p, tris = scenes.noisy_sphere(3, 1)
+    rng = np.random.default_rng(1)
+    ex = rng.random(p.shape).astype(np.float32) if extra else None
+    out = B.dressi_vertex_attrs(dev(p), dev(tris), dev(ex) if extra else None)
+    n = oracle.vertex_normals(p, tris)
+    ref = np.concatenate([n, p] + ([ex] if extra else []), 1)
+    assert_vals_close(host(out), ref, what="vertex_attrs")
+    g = rng.standard_normal(ref.shape).astype(np.float32)
+    gin = rng.standard_normal(p.shape).astype(np.float32)
+    gp = B.dressi_vertex_attrs_bwd(dev(p), dev(tris), dev(g), dev(gin))
+    ref_g = oracle.vertex_normals_bwd(p, tris, g[:, :3]) + g[:, 3:6] + gin
+    assert_grad_close(host(gp), ref_g, what="vertex_attrs_bwd")
+
+
+def _frag_inputs(rng, Bn, N):
+    n = rng.standard_normal((Bn, N, 3)).astype(np.float32)
+    t = rng.standard_normal((Bn, N, 3)).astype(np.float32)
+    m = (np.array([0, 0, 1.0]) + 0.3 * rng.standard_normal((Bn, N, 3))).astype(np.float32)
+    pos = (0.5 * rng.standard_normal((Bn, N, 3))).astype(np.float32)
+    alb = rng.random((Bn, N, 4)).astype(np.float32)
+    env = rng.random((Bn, N, 3)).astype(np.float32)
+    eye = (3 * rng.standard_normal((Bn, 3))).astype(np.float32)
+    tid = rng.integers(-1, 4, (Bn, N)).astype(np.int32)
+    return n, t, m, pos, alb, env, eye, tid
+
+
+@pytest.mark.parametrize("mode,nmap", [(0, False), (1, False), (2, False), (2, True), (1, True)])
+def test_shade(B, mode, nmap):
+    rng = np.random.default_rng(10 + mode + 5 * nmap)
+    Bn, N = 2, 3000
+    n, t, m, pos, alb, env, eye, tid = _frag_inputs(rng, Bn, N)
+    Ca = 3 if mode == 0 else 4
+    # one packed G-buffer row per fragment: n | pos | t | albedo | nmap | env
+    packed = np.concatenate([n, pos, t, alb[..., :Ca], m, env], -1).astype(np.float32)
+    P = dev(packed)
+    o = {"n": 0, "p": 3, "t": 6, "a": 9, "m": 9 + Ca, "e": 12 + Ca}
+    fin = B.frag_in((P, o["n"]), (P, o["p"]) if mode else None, (P, o["t"]) if nmap else None,
+                    (P, o["m"]) if nmap else None, (P, o["a"]), (P, o["e"]) if mode == 2 else None)
+    fin.albedo_channels = Ca
+    col = torch.empty((Bn, N, 3), device="cuda")
+    d = torch.empty((Bn, N, 3), device="cuda")
+    B.dressi_shade(mode, fin, dev(eye), dev(tid), col, d if mode else None)
+    sn = oracle.normal_map(n, t, m, tid) if nmap else n
+    ref = oracle.shade(mode, sn, pos if mode else None, alb[..., :Ca], env if mode == 2 else None, eye, tid)
+    assert_vals_close(host(col), ref, what="shade")
+    if mode:
+        assert_vals_close(host(d), oracle.reflect(sn, pos, eye, tid), what="dir")
+    g = rng.standard_normal((Bn, N, 3)).astype(np.float32)
+    gd = rng.standard_normal((Bn, N, 3)).astype(np.float32) if mode else None
+    G = torch.empty_like(P)
+    fg = B.frag_grad(normal=(G, o["n"]), pos=(G, o["p"]) if mode else None,
+                     tangent=(G, o["t"]) if nmap else None, nmap=(G, o["m"]) if nmap else None,
+                     albedo=(G, o["a"]), env=(G, o["e"]) if mode == 2 else None)
+    B.dressi_shade_bwd(mode, fin, dev(eye), dev(tid), dev(g), dev(gd) if mode else None, fg)
+    Gh = host(G)
+    rgn, rgp, rga, rge = oracle.shade_bwd(mode, sn, pos if mode else None, alb[..., :Ca],
+                                          env if mode == 2 else None, eye, tid, g)
+    if mode:
+        rgn2, rgp2 = oracle.reflect_bwd(sn, pos, eye, tid, gd)
+        rgn, rgp = rgn + rgn2, rgp + rgp2
+    if nmap:
+        rgn, rgt, rgm = oracle.normal_map_bwd(n, t, m, tid, rgn)
+        assert_grad_close(Gh[..., o["t"]:o["t"] + 3], rgt, what="grad tangent")
+        assert_grad_close(Gh[..., o["m"]:o["m"] + 3], rgm, what="grad nmap")
+    assert_grad_close(Gh[..., 0:3], rgn, what="grad normal")
+    assert_grad_close(Gh[..., o["a"]:o["a"] + Ca], rga, what="grad albedo")
+    if mode:
+        assert_grad_close(Gh[..., 3:6], rgp, what="grad pos")
+    if mode == 2:
+        assert_grad_close(Gh[..., o["e"]:o["e"] + 3], rge, what="grad env")
+
+
+def test_loss(B):
+    rng = np.random.default_rng(3)
+    c = rng.random((2, 33, 45, 3)).astype(np.float32)
+    s = rng.random((2, 33, 45)).astype(np.float32)
+    t = rng.random((2, 33, 45, 4)).astype(np.float32)
+    gc = torch.empty((2, 33, 45, 3), device="cuda")
+    gs = torch.empty((2, 33, 45), device="cuda")
+    L = B.dressi_loss_l2(dev(c), dev(s), dev(t), None, gc, gs)
+    Lr, gcr, gsr = oracle.loss_l2(c, s, t)
+    assert abs(float(host(L)[0]) - Lr) < 1e-6 * Lr
+    assert_grad_close(host(gc), gcr)
+    assert_grad_close(host(gs), gsr)
+
+
+# ---------------------------------------------------------------------------
+# whole step
+# ---------------------------------------------------------------------------
+def _gpu_step(scene, views=None):
+    from paper_2204_01386_amd.pipeline import Step, make_target
+    tgt = make_target(scene, views=views)
+    st = Step(scene, views=views, target=tgt)
+    st.run()
+    torch.cuda.synchronize()
+    return st
+
+
+def _compare_step(scene, views=None, env_tol=None, img_tol=1e-5):
+    st = _gpu_step(scene, views)
+    o_st, o_tgt, o_g = ostep.step(scene, views)
+    assert np.array_equal(host(st.tri_id), o_st["tid"]), "tri_id differs"
+    assert np.array_equal(host(st.E), o_st["E"]), "edge mask differs"
+    assert_vals_close(host(st.rgba()), o_st["rgba"], tol=img_tol, what="image")
+    assert_vals_close(host(st.target), o_tgt["rgba"], tol=img_tol, what="target image")
+    L = float(host(st.loss)[0])
+    assert abs(L - o_g["loss"]) <= 1e-5 * o_g["loss"], (L, o_g["loss"])
+    g = st.grads()
+    assert_grad_close(host(g["pos"]), o_g["pos"], what="grad pos")
+    if "color" in o_g:
+        assert_grad_close(host(g["color"]), o_g["color"], what="grad colour")
+    if "tex" in o_g:
+        assert_grad_close(host(g["tex"]), o_g["tex"], what="grad texture")
+    if "env" in o_g:
+        ge, re = host(g["env"]), o_g["env"]
+        rel = np.linalg.norm(ge - re) / np.linalg.norm(re)
+        assert rel < env_tol, f"env gradient rel {rel:.3e}"
+    return st
+
+
+def test_step_config1(B):
+    _compare_step(scenes.config1())
+
+
+def test_step_config2_full(B):
+    _compare_step(scenes.config2())
+
+
+def test_step_config3_two_views(B):
+    # the environment lookup direction is computed in float on the GPU and in
+    # double in the oracle, so rare cube texel / cell choices can differ; that
+    # path is checked exactly stage by stage (test_texture_cube)
+    # The environment term goes through a long single-precision chain
+    # (normal map, normalisations, reflection, cube lookup) whose rounding is
+    # amplified by the environment map's gradient: images get 5e-5 here.
+    s = scenes.config3()
+    _compare_step(s, views=slice(0, 2), env_tol=2e-2, img_tol=5e-5)
+
+
+def test_step_deterministic_and_graph_replay(B):
+    from paper_2204_01386_amd.pipeline import Step, make_target
+    s = scenes.config3(n_views=3, subdiv=4, H=128, tex_size=256, env_size=16)
+    tgt = make_target(s)
+    st = Step(s, target=tgt)
+    st.run()
+    torch.cuda.synchronize()
+    ref = {k: host(v).copy() for k, v in st.grads().items()}
+    st.run()
+    again = {k: host(v) for k, v in st.grads().items()}
+    for k in ref:
+        assert np.array_equal(ref[k], again[k]), f"{k} not bitwise reproducible"
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        st.run()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g):
+        st.run()
+    for rep in range(3):
+        for v in st.grads().values():
+            v.fill_(123.0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for k, v in st.grads().items():
+            assert np.array_equal(host(v), ref[k]), f"replay {rep}: {k} differs from eager"
+    assert B.context().check_status() == 0
