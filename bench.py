@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--profile-steps", type=int, default=20)
     ap.add_argument("--only-graph", action="store_true",
                     help="only the captured-step replays (for external profilers)")
+    ap.add_argument("--copy-ref", type=int, default=0, metavar="MIB",
+                    help="also run a plain device copy of MIB MiB (reference for HBM counters)")
     return ap.parse_args()
 
 
@@ -125,6 +127,13 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.copy_ref:
+        src = torch.ones(args.copy_ref * (1 << 18), dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     scene, desc = scene_for(args.config)
     B = scene.mvp.shape[0]
     tgt = make_target(scene)
@@ -189,8 +198,6 @@ def main():
 
     # ---- per-kernel timing (HIP events around every launch, eager) ---------
     n_prof = args.profile_steps
-    Bd._lib.dressi_profile_start.argtypes = [C.c_int]
-    Bd._lib.dressi_profile_read.argtypes = [C.POINTER(C.c_char_p), C.POINTER(C.c_float), C.c_int]
     cap = 200 * n_prof
     Bd._lib.dressi_profile_start(cap)
     for _ in range(n_prof):

@@ -124,12 +124,36 @@ int dressi_rasterize(dressi_ctx *ctx, const float *pos_clip, const int32_t *tris
  * and dist carried to the clip-space vertices (Rasterize and PeelDepth have no
  * backward of their own; snapping is treated as the identity).  grad_bary
  * [B,K,H,W,2], grad_dist [B,K,H,W] (NULL = zero), tri_id from the forward.
- * Output grad_pos_clip [B,V,4] (the z component is 0).  Deterministic:
- * fragments are sorted by triangle id per tile and reduced in a fixed order. */
+ * frag_index: a fragment index of tri_id (dressi_fragment_index) or NULL to
+ * build one internally; adj: the vertex adjacency of tris (dressi_adjacency)
+ * or NULL.  Output grad_pos_clip [B,V,4] (the z component is 0).
+ * Deterministic: fragments are sorted by triangle id per tile, every triangle
+ * sums its fragments in that order and every vertex its corners in order. */
 int dressi_rasterize_bwd(dressi_ctx *ctx, const float *pos_clip, const int32_t *tris,
                          int B, int V, int T, int H, int W, int K, float r, int cull,
                          const int32_t *tri_id, const float *grad_bary, const float *grad_dist,
-                         float *grad_pos_clip, void *stream);
+                         const void *frag_index, const int32_t *adj, float *grad_pos_clip,
+                         void *stream);
+
+/* ----------------------------------------------------------------------------
+ * Reusable index structures for the deterministic backward reductions.
+ *
+ * dressi_adjacency: for a mesh tris [T,3] over V vertices, writes adj
+ * (V + 1 + 3T int32, caller-owned): offsets [V+1] then, per vertex, its
+ * corners 3t+i in ascending order.  Depends only on the topology: build once
+ * per mesh and pass it to the calls taking `adj`.
+ *
+ * dressi_fragment_index: from tri_id [B,K,H,W] (triangles < T), writes into
+ * `index` (dressi_fragment_index_bytes(...) bytes, caller-owned, opaque) the
+ * fragments of every 16x16 screen tile sorted by triangle id (an LDS bitonic
+ * sort per tile) and, per (view, triangle), the list of tiles holding its
+ * fragments.  Build once per rasterization and pass it to rasterize_bwd and
+ * interpolate_bwd.
+ * ------------------------------------------------------------------------- */
+int dressi_adjacency(dressi_ctx *ctx, const int32_t *tris, int T, int V, int32_t *adj, void *stream);
+size_t dressi_fragment_index_bytes(int B, int K, int H, int W, int T);
+int dressi_fragment_index(dressi_ctx *ctx, const int32_t *tri_id, int B, int K, int H, int W, int T,
+                          void *index, void *stream);
 
 /* ----------------------------------------------------------------------------
  * Attribute interpolation (BuildInterpolate, appendix listing):
@@ -145,11 +169,13 @@ int dressi_interpolate(dressi_ctx *ctx, const float *attr, int Ba, int Va, int C
 /* grad_attr [Ba,Va,C] (summed over views when Ba = 1) and grad_bary
  * [B,K,H,W,2]; either may be NULL.  grad_bary_in (NULL = 0) is added to
  * grad_bary, so several interpolations of one rasterization can chain their
- * barycentric gradients.  Deterministic (sorted per-tile lists). */
+ * barycentric gradients.  frag_index / adj (of attr_tris over Va vertices):
+ * as for dressi_rasterize_bwd, NULL = built internally.  Deterministic. */
 int dressi_interpolate_bwd(dressi_ctx *ctx, const float *attr, int Ba, int Va, int C,
                            const int32_t *attr_tris, int T, const int32_t *tri_id,
                            const float *bary, int B, int K, int H, int W,
-                           const float *grad_out, const float *grad_bary_in, float *grad_attr,
+                           const float *grad_out, const float *grad_bary_in,
+                           const void *frag_index, const int32_t *adj, float *grad_attr,
                            float *grad_bary, void *stream);
 
 /* ----------------------------------------------------------------------------
@@ -215,18 +241,19 @@ int dressi_transform(dressi_ctx *ctx, const float *pos, const float *mvp, int B,
 int dressi_transform_bwd(dressi_ctx *ctx, const float *mvp, int B, int V, const float *grad_clip,
                          float *grad_pos, void *stream);
 
-/* Per-vertex attribute rows out[v] = (n_v, p_v[, extra_v]) with C = 6 or 9,
+/* adj: the mesh adjacency (dressi_adjacency) or NULL to build it internally.
+ * Per-vertex attribute rows out[v] = (n_v, p_v[, extra_v]) with C = 6 or 9,
  * n_v = normalize(sum of (p1-p0) x (p2-p0) over the faces of v) (the
  * listing's BuildNormalCompute; area-weighted, summed in corner order).
  * extra [V,3] (a tangent, a colour, ...) may be NULL (then C = 6). */
 int dressi_vertex_attrs(dressi_ctx *ctx, const float *pos, const int32_t *tris, int V, int T,
-                        const float *extra, float *out, void *stream);
+                        const float *extra, const int32_t *adj, float *out, void *stream);
 /* grad_pos [V,3] from grad_out [V,C] through the normal and position columns,
  * plus grad_pos_in (NULL = 0).  The gradient of `extra` is grad_out[:, 6:9]
  * itself and is not written. */
 int dressi_vertex_attrs_bwd(dressi_ctx *ctx, const float *pos, const int32_t *tris, int V, int T,
-                            int C, const float *grad_out, const float *grad_pos_in,
-                            float *grad_pos, void *stream);
+                            int C, const int32_t *adj, const float *grad_out,
+                            const float *grad_pos_in, float *grad_pos, void *stream);
 
 #define DRESSI_SHADE_LAMBERT 0   /* c = a (0.1 + 0.9 max(0, n.l))                         */
 #define DRESSI_SHADE_PHONG 1     /* c = a_rgb (0.1 + 0.8 max(0,n.l)) + 0.2 a_a max(0,r.v)^32 */

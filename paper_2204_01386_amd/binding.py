@@ -60,18 +60,21 @@ _SIG = {
     "dressi_reserve": [_vp, _sz, _i64],
     "dressi_check_status": [_vp, C.POINTER(C.c_int64), _vp],
     "dressi_rasterize": [_vp, _vp, _vp, _i, _i, _i, _i, _i, _i, _f, _i, _vp, _vp, _vp, _vp],
-    "dressi_rasterize_bwd": [_vp, _vp, _vp, _i, _i, _i, _i, _i, _i, _f, _i, _vp, _vp, _vp, _vp, _vp],
+    "dressi_rasterize_bwd": [_vp, _vp, _vp, _i, _i, _i, _i, _i, _i, _f, _i, _vp, _vp, _vp, _vp, _vp,
+                             _vp, _vp],
     "dressi_interpolate": [_vp, _vp, _i, _i, _i, _vp, _i, _vp, _vp, _i, _i, _i, _i, _vp, _vp],
     "dressi_interpolate_bwd": [_vp, _vp, _i, _i, _i, _vp, _i, _vp, _vp, _i, _i, _i, _i, _vp, _vp,
-                               _vp, _vp, _vp],
+                               _vp, _vp, _vp, _vp, _vp],
     "dressi_texture": [_vp, _vp, C.POINTER(TexDesc), _vp, _vp, _i, _i, _i, _vp, _vp],
     "dressi_texture_bwd": [_vp, _vp, C.POINTER(TexDesc), _vp, _vp, _i, _i, _i, _vp, _vp, _vp, _vp],
     "dressi_softras": [_vp, _vp, _vp, _vp, _i, _i, _i, _i, _i, _f, _f, _i, _vp, _vp, _vp, _vp],
     "dressi_softras_bwd": [_vp, _vp, _vp, _vp, _i, _i, _i, _i, _i, _f, _vp, _vp, _vp, _vp, _vp, _vp],
     "dressi_transform": [_vp, _vp, _vp, _i, _i, _vp, _vp],
     "dressi_transform_bwd": [_vp, _vp, _i, _i, _vp, _vp, _vp],
-    "dressi_vertex_attrs": [_vp, _vp, _vp, _i, _i, _vp, _vp, _vp],
-    "dressi_vertex_attrs_bwd": [_vp, _vp, _vp, _i, _i, _i, _vp, _vp, _vp, _vp],
+    "dressi_vertex_attrs": [_vp, _vp, _vp, _i, _i, _vp, _vp, _vp, _vp],
+    "dressi_vertex_attrs_bwd": [_vp, _vp, _vp, _i, _i, _i, _vp, _vp, _vp, _vp, _vp],
+    "dressi_adjacency": [_vp, _vp, _i, _i, _vp, _vp],
+    "dressi_fragment_index": [_vp, _vp, _i, _i, _i, _i, _i, _vp, _vp],
     "dressi_shade": [_vp, _i, _vp, _vp, _vp, _i, _i64, _vp, _vp, _vp],
     "dressi_shade_bwd": [_vp, _i, _vp, _vp, _vp, _i, _i64, _vp, _vp, _vp, _vp],
     "dressi_loss_l2": [_vp, _vp, _vp, _vp, _i, _i, _i, _vp, _vp, _vp, _vp],
@@ -84,8 +87,15 @@ _lib.dressi_last_error.argtypes = [_vp]
 _lib.dressi_last_error.restype = C.c_char_p
 _lib.dressi_scratch_bytes.argtypes = [_i, _i, _i, _i, _i, _i, _f, _i, _i, _i64, _i]
 _lib.dressi_scratch_bytes.restype = C.c_size_t
+_lib.dressi_fragment_index_bytes.argtypes = [_i, _i, _i, _i, _i]
+_lib.dressi_fragment_index_bytes.restype = C.c_size_t
+_lib.dressi_profile_start.argtypes = [_i]
+_lib.dressi_profile_start.restype = C.c_int
+_lib.dressi_profile_read.argtypes = [C.POINTER(C.c_char_p), C.POINTER(C.c_float), _i]
+_lib.dressi_profile_read.restype = C.c_int
 
-EXPORTED = sorted(list(_SIG) + ["dressi_last_error", "dressi_scratch_bytes"])
+EXPORTED = sorted(list(_SIG) + ["dressi_last_error", "dressi_scratch_bytes", "dressi_fragment_index_bytes",
+                                "dressi_profile_start", "dressi_profile_read"])
 
 
 class DressiError(RuntimeError):
@@ -175,7 +185,8 @@ def dressi_rasterize(pos_clip, tris, H, W, K=1, r=0.0, cull=0):
     return tri_id, bary, dist
 
 
-def dressi_rasterize_bwd(pos_clip, tris, tri_id, grad_bary, grad_dist=None, r=0.0, cull=0):
+def dressi_rasterize_bwd(pos_clip, tris, tri_id, grad_bary, grad_dist=None, r=0.0, cull=0,
+                         frag_index=None, adj=None):
     _need(pos_clip, torch.float32, "pos_clip")
     _need(tris, torch.int32, "tris")
     _need(tri_id, torch.int32, "tri_id")
@@ -188,7 +199,8 @@ def dressi_rasterize_bwd(pos_clip, tris, tri_id, grad_bary, grad_dist=None, r=0.
     ctx = context(pos_clip.device.index)
     ctx.check(_lib.dressi_rasterize_bwd(ctx.handle, _ptr(pos_clip), _ptr(tris), B, V, tris.shape[0],
                                         H, W, K, float(r), int(cull), _ptr(tri_id), _ptr(grad_bary),
-                                        _ptr(grad_dist), _ptr(g), _stream()), "dressi_rasterize_bwd")
+                                        _ptr(grad_dist), _ptr(frag_index), _ptr(adj), _ptr(g), _stream()),
+              "dressi_rasterize_bwd")
     return g
 
 
@@ -212,7 +224,7 @@ def dressi_interpolate(attr, attr_tris, tri_id, bary):
 
 
 def dressi_interpolate_bwd(attr, attr_tris, tri_id, bary, grad_out, need_attr=True, need_bary=True,
-                           grad_bary_in=None):
+                           grad_bary_in=None, frag_index=None, adj=None):
     a = _need(_attr3(attr), torch.float32, "attr")
     _need(grad_out, torch.float32, "grad_out")
     Ba, Va, Cc = a.shape
@@ -222,8 +234,8 @@ def dressi_interpolate_bwd(attr, attr_tris, tri_id, bary, grad_out, need_attr=Tr
     ctx = context(a.device.index)
     ctx.check(_lib.dressi_interpolate_bwd(ctx.handle, _ptr(a), Ba, Va, Cc, _ptr(attr_tris),
                                           attr_tris.shape[0], _ptr(tri_id), _ptr(bary), B, K, H, W,
-                                          _ptr(grad_out), _ptr(grad_bary_in), _ptr(ga), _ptr(gb),
-                                          _stream()), "dressi_interpolate_bwd")
+                                          _ptr(grad_out), _ptr(grad_bary_in), _ptr(frag_index), _ptr(adj),
+                                          _ptr(ga), _ptr(gb), _stream()), "dressi_interpolate_bwd")
     if ga is not None and attr.dim() == 2:
         ga = ga[0]
     return ga, gb
@@ -324,25 +336,26 @@ def dressi_transform_bwd(mvp, grad_clip):
     return out
 
 
-def dressi_vertex_attrs(pos, tris, extra=None):
+def dressi_vertex_attrs(pos, tris, extra=None, adj=None):
     _need(pos, torch.float32, "pos")
     _need(tris, torch.int32, "tris")
     V, T = pos.shape[0], tris.shape[0]
     C_ = 9 if extra is not None else 6
     out = torch.empty((V, C_), dtype=torch.float32, device=pos.device)
     ctx = context(pos.device.index)
-    ctx.check(_lib.dressi_vertex_attrs(ctx.handle, _ptr(pos), _ptr(tris), V, T, _ptr(extra), _ptr(out),
-                                       _stream()), "dressi_vertex_attrs")
+    ctx.check(_lib.dressi_vertex_attrs(ctx.handle, _ptr(pos), _ptr(tris), V, T, _ptr(extra), _ptr(adj),
+                                       _ptr(out), _stream()), "dressi_vertex_attrs")
     return out
 
 
-def dressi_vertex_attrs_bwd(pos, tris, grad_out, grad_pos_in=None):
+def dressi_vertex_attrs_bwd(pos, tris, grad_out, grad_pos_in=None, adj=None):
     _need(grad_out, torch.float32, "grad_out")
     V, T = pos.shape[0], tris.shape[0]
     out = torch.empty((V, 3), dtype=torch.float32, device=pos.device)
     ctx = context(pos.device.index)
     ctx.check(_lib.dressi_vertex_attrs_bwd(ctx.handle, _ptr(pos), _ptr(tris), V, T, grad_out.shape[1],
-                                           _ptr(grad_out), _ptr(grad_pos_in), _ptr(out), _stream()),
+                                           _ptr(adj), _ptr(grad_out), _ptr(grad_pos_in), _ptr(out),
+                                           _stream()),
               "dressi_vertex_attrs_bwd")
     return out
 
@@ -409,3 +422,26 @@ def dressi_loss_l2(color, sil, target, loss=None, grad_color=None, grad_sil=None
                                   _ptr(loss), _ptr(grad_color), _ptr(grad_sil), _stream()),
               "dressi_loss_l2")
     return loss
+
+
+def dressi_adjacency(tris, V):
+    """Vertex -> corner adjacency of a mesh (int32 [V + 1 + 3T]); build once per mesh."""
+    _need(tris, torch.int32, "tris")
+    T = tris.shape[0]
+    adj = torch.empty(V + 1 + 3 * T, dtype=torch.int32, device=tris.device)
+    ctx = context(tris.device.index)
+    ctx.check(_lib.dressi_adjacency(ctx.handle, _ptr(tris), T, V, _ptr(adj), _stream()), "dressi_adjacency")
+    return adj
+
+
+def dressi_fragment_index(tri_id, T, out=None):
+    """Per-tile triangle-sorted fragment index of tri_id (opaque uint8 buffer)."""
+    _need(tri_id, torch.int32, "tri_id")
+    B, K, H, W = tri_id.shape
+    nbytes = int(_lib.dressi_fragment_index_bytes(B, K, H, W, T))
+    if out is None:
+        out = torch.empty(nbytes, dtype=torch.uint8, device=tri_id.device)
+    ctx = context(tri_id.device.index)
+    ctx.check(_lib.dressi_fragment_index(ctx.handle, _ptr(tri_id), B, K, H, W, T, _ptr(out), _stream()),
+              "dressi_fragment_index")
+    return out

@@ -42,6 +42,7 @@ extern "C" int dressi_destroy(dressi_ctx *ctx) {
     (void)hipDeviceSynchronize();
     if (ctx->scratch) (void)hipFree(ctx->scratch);
     if (ctx->status) (void)hipFree(ctx->status);
+    if (ctx->counters) (void)hipFree(ctx->counters);
     delete ctx;
     return DRESSI_OK;
 }
@@ -81,6 +82,32 @@ int dressi_scratch(dressi_ctx *ctx, size_t bytes, hipStream_t stream) {
     return grow(ctx, bytes);
 }
 
+int dressi_counters(dressi_ctx *ctx, size_t n, hipStream_t stream) {
+    if (n <= ctx->counters_n) return DRESSI_OK;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    hipError_t e = hipStreamIsCapturing(stream, &cs);
+    if (e != hipSuccess) return dressi_hip_check(ctx, e, "hipStreamIsCapturing");
+    if (cs != hipStreamCaptureStatusNone)
+        return dressi_fail(ctx, DRESSI_ENOMEM, "counter array too small during stream capture: "
+                                               "run the call once before capturing");
+    size_t nn = n + n / 4 + 4096;
+    e = hipDeviceSynchronize();
+    if (e != hipSuccess) return dressi_hip_check(ctx, e, "synchronize before counter growth");
+    if (ctx->counters) (void)hipFree(ctx->counters);
+    ctx->counters = nullptr;
+    ctx->counters_n = 0;
+    e = hipMalloc(&ctx->counters, nn * sizeof(int32_t));
+    if (e == hipSuccess) e = hipMemset(ctx->counters, 0, nn * sizeof(int32_t));
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        if (ctx->counters) (void)hipFree(ctx->counters);
+        ctx->counters = nullptr;
+        return dressi_fail(ctx, DRESSI_ENOMEM, std::string("counter allocation failed: ") + hipGetErrorString(e));
+    }
+    ctx->counters_n = nn;
+    return DRESSI_OK;
+}
+
 extern "C" int dressi_reserve(dressi_ctx *ctx, size_t bytes, int64_t bin_entries) {
     if (!ctx) return DRESSI_EINVAL;
     if (bin_entries > ctx->bin_capacity) ctx->bin_capacity = bin_entries;
@@ -102,7 +129,7 @@ extern "C" int dressi_check_status(dressi_ctx *ctx, int64_t *needed, void *strea
         if (e != hipSuccess) return dressi_hip_check(ctx, e, "clearing device status");
         return dressi_fail(ctx, DRESSI_EOVERFLOW,
                            "tile-bin capacity exceeded: " + std::to_string(h[1]) +
-                               " entries needed; call dressi_reserve and rerun");
+                               " triangles per tile needed; call dressi_reserve and rerun");
     }
     return DRESSI_OK;
 }

@@ -17,8 +17,10 @@ struct dressi_ctx {
     int device = 0;
     void *scratch = nullptr;    // device arena, reused by every call on this context
     size_t scratch_bytes = 0;
-    int64_t bin_capacity = 0;   // entries of the tile-bin array
-    int64_t *status = nullptr;  // device: [0] overflow flag, [1] entries needed
+    int64_t bin_capacity = 0;   // triangles per screen tile bin (0 = automatic)
+    int64_t *status = nullptr;  // device: [0] overflow flag, [1] bin capacity needed
+    int32_t *counters = nullptr;  // device counters kept at zero between calls
+    size_t counters_n = 0;
     std::string err;
 };
 
@@ -31,6 +33,11 @@ int dressi_hip_check(dressi_ctx *ctx, hipError_t e, const char *what);
 // fails with DRESSI_ENOMEM while `stream` is capturing.
 int dressi_scratch(dressi_ctx *ctx, size_t bytes, hipStream_t stream);
 int dressi_launch_check(dressi_ctx *ctx, const char *what);
+// Makes sure ctx->counters holds at least n int32 counters, all zero.  The
+// kernels that use them count up and then back down (or reset what they
+// read), so they are zero again when a call ends.  Grows only outside
+// stream capture.
+int dressi_counters(dressi_ctx *ctx, size_t n, hipStream_t stream);
 
 // Optional per-kernel timing with HIP events (eager runs only): every launch
 // goes through DR_LAUNCH, which brackets it with event records while the
@@ -67,18 +74,27 @@ void dressi_fill_f32(float *p, float v, int64_t n, hipStream_t s);
 size_t dressi_scan_tmp_bytes(int64_t n);
 void dressi_exclusive_scan(const int32_t *in, int32_t *out, int64_t n, void *tmp, hipStream_t s);
 
-// vertex -> corner adjacency: offsets [V+1], corners [3T] (corner = 3t+i)
+// vertex -> corner adjacency: offsets [V+1], corners [3T] (corner = 3t+i),
+// stored in one int32 buffer of V+1+3T entries (offsets first)
 struct Adjacency {
     int32_t *offsets;
     int32_t *corners;
 };
-size_t dressi_adjacency_bytes(int V, int T);
-void dressi_build_adjacency(const int32_t *tris, int T, int V, void *scratch, Adjacency &adj,
-                            hipStream_t s);
+static inline Adjacency adjacency_view(const int32_t *buf, int V) {
+    Adjacency a;
+    a.offsets = const_cast<int32_t *>(buf);
+    a.corners = const_cast<int32_t *>(buf) + V + 1;
+    return a;
+}
+static inline size_t adjacency_buf_bytes(int V, int T) { return sizeof(int32_t) * ((size_t)V + 1 + 3 * (size_t)T); }
+size_t dressi_adjacency_tmp_bytes(int V);
+void dressi_build_adjacency_into(const int32_t *tris, int T, int V, int32_t *buf, void *tmp,
+                                 hipStream_t s);
 
 // ---------------------------------------------------------------------------
-// per-tile fragment lists (raster.hip): fragments of each tile sorted by
-// triangle id, used by every deterministic backward reduction
+// fragment index (raster.hip): the fragments of each tile sorted by triangle
+// id, and its transpose (the tiles of each triangle).  Used by every
+// deterministic backward reduction; built once per rasterization.
 // ---------------------------------------------------------------------------
 struct FragLists {
     int32_t *n_frag;    // [B*nTiles] valid fragments in the tile
@@ -87,20 +103,17 @@ struct FragLists {
     int32_t *rec_tri;   // [B*nTiles*256*K] distinct triangle ids, ascending
     int32_t *rec_start; // [B*nTiles*256*K] first sorted fragment of each triangle
 };
-size_t dressi_fraglists_bytes(int B, int H, int W, int K);
-void dressi_build_fraglists(const int32_t *tri_id, int B, int K, int H, int W, void *scratch,
-                            FragLists &fl, hipStream_t s);
-
-// transpose of the per-tile records: for every (view, triangle) the tiles in
-// which it has fragments, as (tile index b*nTiles+tile, record index) pairs in
-// ascending tile order
+// for every (view, triangle) the tiles in which it has fragments, as
+// (tile index b*nTiles+tile, record index) pairs in ascending tile order
 struct TriTiles {
     int32_t *offsets;   // [B*T+1]
-    int2 *entries;      // [total records]
+    int2 *entries;      // [B*nTiles*256*K]
 };
-size_t dressi_tritiles_bytes(int B, int T, int H, int W, int K);
-void dressi_build_tritiles(const FragLists &fl, int B, int T, int K, int H, int W, void *scratch,
-                           TriTiles &tt, hipStream_t s);
+size_t dressi_fragindex_bytes(int B, int K, int H, int W, int T);
+void dressi_fragindex_view(void *base, int B, int K, int H, int W, int T, FragLists &fl, TriTiles &tt);
+size_t dressi_fragindex_tmp_bytes(int B, int T);
+void dressi_build_fragindex(const int32_t *tri_id, int B, int K, int H, int W, int T, void *base,
+                            void *tmp, int32_t *zero_counts, hipStream_t s);
 
 __host__ __device__ static inline int tiles_x(int W) { return (W + DRESSI_TILE - 1) / DRESSI_TILE; }
 __host__ __device__ static inline int tiles_y(int H) { return (H + DRESSI_TILE - 1) / DRESSI_TILE; }

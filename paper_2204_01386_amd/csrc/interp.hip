@@ -9,6 +9,8 @@
 // ascending order.  No float atomics.
 #include "dressi_internal.h"
 
+#include <algorithm>
+
 #define IB_CH 16   // channels per pass of the per-triangle gather
 
 __global__ void k_interp(const float *__restrict__ attr, int Ba, int Va, int C,
@@ -98,14 +100,103 @@ __global__ void k_interp_bwd_bary(const float *__restrict__ attr, int Ba, int Va
     grad_bary[o] = make_float2(acc.x + g0, acc.y + g1);
 }
 
-// per (view or shared, triangle, channel chunk): sum over fragments of b_i g
-__global__ void k_interp_bwd_tri(int B, int Ba, int T, int K, int H, int W, int C, int ntx, FragLists fl,
-                                 TriTiles tt, const float2 *__restrict__ bary,
-                                 const float *__restrict__ grad_out, float *__restrict__ corner_grad) {
+// per tile: every fragment's (b0, b1, g_0..g_{C-1}) in LDS; each triangle's
+// fragments (consecutive in the tile's sorted list) are summed into one
+// record of b_i g_c for its three corners.  Also writes grad_bary.
+__global__ void __launch_bounds__(DRESSI_TILE_PIX)
+    k_interp_bwd_tile(const float *__restrict__ attr, int Ba, int Va, int C,
+                      const int32_t *__restrict__ attr_tris, int T, const int32_t *__restrict__ tri_id,
+                      const float2 *__restrict__ bary, int K, int H, int W, int ntx, int nt, FragLists fl,
+                      const float *__restrict__ grad_out, const float2 *__restrict__ gb_in,
+                      float2 *__restrict__ grad_bary, float *__restrict__ partial) {
+    extern __shared__ float vals[];   // [K*256][C+2]
+    const int bt = blockIdx.x;
+    const int b = bt / nt, tile = bt - b * nt;
+    const int tx = tile % ntx, ty = tile / ntx;
+    const int p = threadIdx.x;
+    const int x = tx * DRESSI_TILE + (p & (DRESSI_TILE - 1));
+    const int y = ty * DRESSI_TILE + p / DRESSI_TILE;
+    const int S = C + 2;
+    const float *ab = attr + (Ba == 1 ? 0 : (int64_t)b * Va * C);
+    if (x < W && y < H) {
+        for (int k = 0; k < K; k++) {
+            int64_t o = (((int64_t)b * K + k) * H + y) * W + x;
+            int t = tri_id[o];
+            int v0 = -1, v1 = -1, v2 = -1;
+            if (t >= 0 && t < T) {
+                v0 = attr_tris[3 * (int64_t)t];
+                v1 = attr_tris[3 * (int64_t)t + 1];
+                v2 = attr_tris[3 * (int64_t)t + 2];
+            }
+            bool ok = v0 >= 0 && v0 < Va && v1 >= 0 && v1 < Va && v2 >= 0 && v2 < Va;
+            float2 acc = gb_in ? gb_in[o] : make_float2(0.0f, 0.0f);
+            const float *g = grad_out + o * C;
+            float *dst = vals + (k * DRESSI_TILE_PIX + p) * S;
+            if (ok) {
+                float2 w = bary[o];
+                dst[0] = w.x;
+                dst[1] = w.y;
+                const float *a0 = ab + (int64_t)v0 * C, *a1 = ab + (int64_t)v1 * C, *a2 = ab + (int64_t)v2 * C;
+                float g0 = 0.0f, g1 = 0.0f;
+                for (int c = 0; c < C; c++) {
+                    float gc = g[c];
+                    dst[2 + c] = gc;
+                    g0 += gc * (a0[c] - a2[c]);
+                    g1 += gc * (a1[c] - a2[c]);
+                }
+                acc.x += g0;
+                acc.y += g1;
+            } else if (t >= 0) {
+                // a fragment whose attribute triangle is invalid contributes nothing
+                dst[0] = 0.0f;
+                dst[1] = 0.0f;
+                for (int c = 0; c < C; c++) dst[2 + c] = 0.0f;
+            }
+            if (grad_bary) grad_bary[o] = acc;
+        }
+    }
+    __syncthreads();
+    const int nf = fl.n_frag[bt];
+    const int nr = fl.n_rec[bt];
+    const int64_t base = (int64_t)bt * DRESSI_TILE_PIX * K;
+    for (int r = p; r < nr; r += DRESSI_TILE_PIX) {
+        int j0 = fl.rec_start[base + r];
+        int j1 = (r + 1 < nr) ? fl.rec_start[base + r + 1] : nf;
+        float *dst = partial + (base + r) * 3 * C;
+        for (int c0 = 0; c0 < C; c0 += IB_CH) {
+            float acc[3][IB_CH];
+#pragma unroll
+            for (int i = 0; i < 3; i++)
+#pragma unroll
+                for (int c = 0; c < IB_CH; c++) acc[i][c] = 0.0f;
+            for (int j = j0; j < j1; j++) {
+                const float *v = vals + (int)fl.frag[base + j] * S;
+                float w0 = v[0], w1 = v[1], w2 = 1.0f - w0 - w1;
+#pragma unroll
+                for (int c = 0; c < IB_CH; c++) {
+                    if (c0 + c < C) {
+                        float gc = v[2 + c0 + c];
+                        acc[0][c] += w0 * gc;
+                        acc[1][c] += w1 * gc;
+                        acc[2][c] += w2 * gc;
+                    }
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < 3; i++)
+#pragma unroll
+                for (int c = 0; c < IB_CH; c++)
+                    if (c0 + c < C) dst[i * C + c0 + c] = acc[i][c];
+        }
+    }
+}
+
+// per (shared or per-view, triangle): its records summed over views and tiles
+__global__ void k_interp_bwd_sum(int B, int Ba, int T, int K, int C, TriTiles tt,
+                                 const float *__restrict__ partial, float *__restrict__ corner_grad) {
     int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int chunk = blockIdx.y;
     const int c0 = chunk * IB_CH;
-    const int nc = min(IB_CH, C - c0);
     if (gid >= (int64_t)Ba * T) return;
     int ba = (int)(gid / T), t = (int)(gid - (int64_t)ba * T);
     float acc[3][IB_CH];
@@ -113,37 +204,17 @@ __global__ void k_interp_bwd_tri(int B, int Ba, int T, int K, int H, int W, int 
     for (int i = 0; i < 3; i++)
 #pragma unroll
         for (int c = 0; c < IB_CH; c++) acc[i][c] = 0.0f;
-    const int nt = ntx * tiles_y(H);
     int b0 = (Ba == 1) ? 0 : ba, b1 = (Ba == 1) ? B : ba + 1;
     for (int b = b0; b < b1; b++) {
         int64_t key = (int64_t)b * T + t;
         for (int e = tt.offsets[key]; e < tt.offsets[key + 1]; e++) {
             int2 ent = tt.entries[e];
-            int64_t bt = ent.x;
-            int tile = (int)(bt - (int64_t)b * nt);
-            int tx = tile % ntx, ty = tile / ntx;
-            int64_t base = bt * DRESSI_TILE_PIX * K;
-            int r = ent.y;
-            int j0 = fl.rec_start[base + r];
-            int j1 = (r + 1 < fl.n_rec[bt]) ? fl.rec_start[base + r + 1] : fl.n_frag[bt];
-            for (int j = j0; j < j1; j++) {
-                int f = fl.frag[base + j];
-                int k = f >> 8, pl = f & 255;
-                int x = tx * DRESSI_TILE + (pl & 15), y = ty * DRESSI_TILE + (pl >> 4);
-                int64_t o = (((int64_t)b * K + k) * H + y) * W + x;
-                float2 w = bary[o];
-                float w2 = 1.0f - w.x - w.y;
-                const float *g = grad_out + o * C + c0;
+            const float *v = partial + ((int64_t)ent.x * DRESSI_TILE_PIX * K + ent.y) * 3 * C;
 #pragma unroll
-                for (int c = 0; c < IB_CH; c++) {
-                    if (c < nc) {
-                        float gc = g[c];
-                        acc[0][c] += w.x * gc;
-                        acc[1][c] += w.y * gc;
-                        acc[2][c] += w2 * gc;
-                    }
-                }
-            }
+            for (int i = 0; i < 3; i++)
+#pragma unroll
+                for (int c = 0; c < IB_CH; c++)
+                    if (c0 + c < C) acc[i][c] += v[i * C + c0 + c];
         }
     }
     float *cg = corner_grad + gid * 3 * C;
@@ -151,7 +222,7 @@ __global__ void k_interp_bwd_tri(int B, int Ba, int T, int K, int H, int W, int 
     for (int i = 0; i < 3; i++)
 #pragma unroll
         for (int c = 0; c < IB_CH; c++)
-            if (c < nc) cg[i * C + c0 + c] = acc[i][c];
+            if (c0 + c < C) cg[i * C + c0 + c] = acc[i][c];
 }
 
 __global__ void k_interp_vertex_gather(const float *__restrict__ corner_grad, Adjacency adj, int Ba,
@@ -174,41 +245,64 @@ extern "C" int dressi_interpolate_bwd(dressi_ctx *ctx, const float *attr, int Ba
                                       const int32_t *attr_tris, int T, const int32_t *tri_id,
                                       const float *bary, int B, int K, int H, int W,
                                       const float *grad_out, const float *grad_bary_in,
-                                      float *grad_attr, float *grad_bary, void *stream) {
+                                      const void *frag_index, const int32_t *adj, float *grad_attr,
+                                      float *grad_bary, void *stream) {
     int rc = check_interp(ctx, attr, Ba, Va, C, attr_tris, T, tri_id, bary, B, K, H, W);
     if (rc) return rc;
     int64_t n = (int64_t)B * K * H * W;
     if (n > 0 && !grad_out) return dressi_fail(ctx, DRESSI_EINVAL, "interpolate_bwd: null grad_out");
     hipStream_t st = (hipStream_t)stream;
-    if (grad_bary && n > 0)
-        DR_LAUNCH("k_interp_bwd_bary", (k_interp_bwd_bary), (int)((n + 255) / 256), 256, 0, st, 
-            attr, Ba, Va, C, attr_tris, T, tri_id, (int64_t)K * H * W, n, grad_out,
-            reinterpret_cast<const float2 *>(grad_bary_in), reinterpret_cast<float2 *>(grad_bary));
     if (grad_attr && Va > 0) {
+        int ntx = tiles_x(W), nt = ntx * tiles_y(H);
         Carver c;
-        size_t o_fl = c.take(dressi_fraglists_bytes(B, H, W, K));
-        size_t o_tt = c.take(dressi_tritiles_bytes(B, T, H, W, K));
-        size_t o_adj = c.take(dressi_adjacency_bytes(Va, T));
+        size_t o_fi = frag_index ? 0 : c.take(dressi_fragindex_bytes(B, K, H, W, T));
+        size_t o_adj = adj ? 0 : c.take(adjacency_buf_bytes(Va, T));
+        size_t o_tmp = c.take(std::max(frag_index ? (size_t)0 : dressi_fragindex_tmp_bytes(B, T),
+                                       adj ? (size_t)0 : dressi_adjacency_tmp_bytes(Va)));
+        size_t o_part = c.take(sizeof(float) * (size_t)B * nt * DRESSI_TILE_PIX * K * 3 * C);
         size_t o_cg = c.take(sizeof(float) * 3 * (size_t)C * Ba * T);
         rc = dressi_scratch(ctx, c.off, st);
         if (rc) return rc;
+        if (!frag_index) {
+            rc = dressi_counters(ctx, (size_t)B * T, st);
+            if (rc) return rc;
+        }
         void *S = ctx->scratch;
+        void *fi = const_cast<void *>(frag_index);
+        if (!fi) {
+            fi = at<void>(S, o_fi);
+            dressi_build_fragindex(tri_id, B, K, H, W, T, fi, at<void>(S, o_tmp), ctx->counters, st);
+        }
         FragLists fl;
         TriTiles tt;
-        Adjacency adj;
-        dressi_build_fraglists(tri_id, B, K, H, W, at<void>(S, o_fl), fl, st);
-        dressi_build_tritiles(fl, B, T, K, H, W, at<void>(S, o_tt), tt, st);
-        dressi_build_adjacency(attr_tris, T, Va, at<void>(S, o_adj), adj, st);
+        dressi_fragindex_view(fi, B, K, H, W, T, fl, tt);
+        const int32_t *ab = adj;
+        if (!ab) {
+            int32_t *buf = at<int32_t>(S, o_adj);
+            dressi_build_adjacency_into(attr_tris, T, Va, buf, at<void>(S, o_tmp), st);
+            ab = buf;
+        }
+        Adjacency A = adjacency_view(ab, Va);
+        float *part = at<float>(S, o_part);
         float *cg = at<float>(S, o_cg);
+        if ((int64_t)B * nt > 0)
+            DR_LAUNCH("k_interp_bwd_tile", (k_interp_bwd_tile), B * nt, DRESSI_TILE_PIX,
+                      sizeof(float) * (size_t)(C + 2) * DRESSI_TILE_PIX * K, st, attr, Ba, Va, C, attr_tris, T,
+                      tri_id, reinterpret_cast<const float2 *>(bary), K, H, W, ntx, nt, fl, grad_out,
+                      reinterpret_cast<const float2 *>(grad_bary_in), reinterpret_cast<float2 *>(grad_bary),
+                      part);
         int64_t ntri = (int64_t)Ba * T;
         if (ntri > 0) {
-            dim3 g((unsigned)((ntri + 127) / 128), (unsigned)((C + IB_CH - 1) / IB_CH));
-            DR_LAUNCH("k_interp_bwd_tri", (k_interp_bwd_tri), g, 128, 0, st, B, Ba, T, K, H, W, C, tiles_x(W), fl, tt,
-                                                 reinterpret_cast<const float2 *>(bary), grad_out, cg);
+            dim3 g((unsigned)((ntri + 255) / 256), (unsigned)((C + IB_CH - 1) / IB_CH));
+            DR_LAUNCH("k_interp_bwd_sum", (k_interp_bwd_sum), g, 256, 0, st, B, Ba, T, K, C, tt, part, cg);
         }
         int64_t ng = (int64_t)Ba * Va * C;
-        DR_LAUNCH("k_interp_vertex_gather", (k_interp_vertex_gather), (int)((ng + 255) / 256), 256, 0, st, cg, adj, Ba, Va, T, C,
-                                                                          grad_attr);
+        DR_LAUNCH("k_interp_vertex_gather", (k_interp_vertex_gather), (int)((ng + 255) / 256), 256, 0, st,
+                  cg, A, Ba, Va, T, C, grad_attr);
+    } else if (grad_bary && n > 0) {
+        DR_LAUNCH("k_interp_bwd_bary", (k_interp_bwd_bary), (int)((n + 255) / 256), 256, 0, st,
+                  attr, Ba, Va, C, attr_tris, T, tri_id, (int64_t)K * H * W, n, grad_out,
+                  reinterpret_cast<const float2 *>(grad_bary_in), reinterpret_cast<float2 *>(grad_bary));
     }
     return dressi_launch_check(ctx, "interpolate_bwd");
 }

@@ -119,6 +119,35 @@ __global__ void __launch_bounds__(SCAN_BS) k_scan_apply(const int32_t *in, int32
     if (blockIdx.x == gridDim.x - 1 && threadIdx.x == SCAN_BS - 1) out[n] = ex;
 }
 
+// whole scan in one workgroup (small n): chunks of 4096 with a running carry
+__global__ void __launch_bounds__(1024) k_scan_single(const int32_t *in, int32_t *out, int64_t n) {
+    __shared__ int wsum[16];
+    __shared__ int carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int64_t c0 = 0; c0 < n; c0 += 4096) {
+        int64_t i0 = c0 + 4 * (int64_t)threadIdx.x;
+        int v[4];
+        int sum = 0;
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            v[j] = i0 + j < n ? in[i0 + j] : 0;
+            sum += v[j];
+        }
+        int total;
+        int ex = block_exclusive_scan<1024>(sum, total, wsum) + carry;
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            if (i0 + j < n) out[i0 + j] = ex;
+            ex += v[j];
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) carry += total;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[n] = carry;
+}
+
 size_t dressi_scan_tmp_bytes(int64_t n) {
     int64_t nb = (n + SCAN_CHUNK - 1) / SCAN_CHUNK;
     return (size_t)(nb + 1) * sizeof(int32_t);
@@ -127,6 +156,10 @@ size_t dressi_scan_tmp_bytes(int64_t n) {
 void dressi_exclusive_scan(const int32_t *in, int32_t *out, int64_t n, void *tmp, hipStream_t s) {
     if (n <= 0) {
         dressi_fill_i32(out, 0, 1, s);
+        return;
+    }
+    if (n <= 16384) {
+        DR_LAUNCH("k_scan_single", (k_scan_single), 1, 1024, 0, s, in, out, n);
         return;
     }
     int nb = (int)((n + SCAN_CHUNK - 1) / SCAN_CHUNK);
@@ -173,31 +206,39 @@ __global__ void k_sort_corners(const int32_t *offsets, int32_t *corners, int V) 
     }
 }
 
-size_t dressi_adjacency_bytes(int V, int T) {
+size_t dressi_adjacency_tmp_bytes(int V) {
     Carver c;
-    c.take(sizeof(int32_t) * (V + 1));        // offsets
-    c.take(sizeof(int32_t) * 3 * (size_t)T);  // corners
-    c.take(sizeof(int32_t) * V);              // counts
-    c.take(sizeof(int32_t) * V);              // cursor
+    c.take(sizeof(int32_t) * (size_t)V);   // counts
+    c.take(sizeof(int32_t) * (size_t)V);   // cursor
     c.take(dressi_scan_tmp_bytes(V));
     return c.off;
 }
 
-void dressi_build_adjacency(const int32_t *tris, int T, int V, void *scratch, Adjacency &adj,
-                            hipStream_t s) {
+void dressi_build_adjacency_into(const int32_t *tris, int T, int V, int32_t *buf, void *tmp,
+                                 hipStream_t s) {
+    Adjacency adj = adjacency_view(buf, V);
     Carver c;
-    adj.offsets = at<int32_t>(scratch, c.take(sizeof(int32_t) * (V + 1)));
-    adj.corners = at<int32_t>(scratch, c.take(sizeof(int32_t) * 3 * (size_t)T));
-    int32_t *counts = at<int32_t>(scratch, c.take(sizeof(int32_t) * V));
-    int32_t *cursor = at<int32_t>(scratch, c.take(sizeof(int32_t) * V));
-    void *tmp = at<void>(scratch, c.take(dressi_scan_tmp_bytes(V)));
+    int32_t *counts = at<int32_t>(tmp, c.take(sizeof(int32_t) * (size_t)V));
+    int32_t *cursor = at<int32_t>(tmp, c.take(sizeof(int32_t) * (size_t)V));
+    void *stmp = at<void>(tmp, c.take(dressi_scan_tmp_bytes(V)));
     int64_t n3 = 3 * (int64_t)T;
-    dressi_fill_i32(counts, 0, V, s);
-    dressi_fill_i32(cursor, 0, V, s);
+    dressi_fill_i32(counts, 0, 2 * (int64_t)((sizeof(int32_t) * (size_t)V + 255) / 256 * 64), s);
     if (n3 > 0) DR_LAUNCH("k_count_corners", (k_count_corners), (int)((n3 + 255) / 256), 256, 0, s, tris, n3, V, counts);
-    dressi_exclusive_scan(counts, adj.offsets, V, tmp, s);
+    dressi_exclusive_scan(counts, adj.offsets, V, stmp, s);
     if (n3 > 0)
         DR_LAUNCH("k_place_corners", (k_place_corners), (int)((n3 + 255) / 256), 256, 0, s, tris, n3, V, adj.offsets, cursor,
                                                                adj.corners);
     if (V > 0) DR_LAUNCH("k_sort_corners", (k_sort_corners), (V + 255) / 256, 256, 0, s, adj.offsets, adj.corners, V);
+}
+
+extern "C" int dressi_adjacency(dressi_ctx *ctx, const int32_t *tris, int T, int V, int32_t *adj,
+                                void *stream) {
+    if (!ctx) return DRESSI_EINVAL;
+    if (T < 0 || V < 0) return dressi_fail(ctx, DRESSI_EINVAL, "adjacency: bad dimensions");
+    if (!adj || (T > 0 && !tris)) return dressi_fail(ctx, DRESSI_EINVAL, "adjacency: null pointer");
+    hipStream_t st = (hipStream_t)stream;
+    int rc = dressi_scratch(ctx, dressi_adjacency_tmp_bytes(V), st);
+    if (rc) return rc;
+    dressi_build_adjacency_into(tris, T, V, adj, ctx->scratch, st);
+    return dressi_launch_check(ctx, "adjacency");
 }

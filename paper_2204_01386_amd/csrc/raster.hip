@@ -16,131 +16,120 @@
 // reproducible.
 #include "dressi_internal.h"
 
+#include <algorithm>
 #include <cfloat>
 
 // ---------------------------------------------------------------------------
 // setup, counting and bin fill
+//
+// Neighbouring triangle ids are mostly neighbours on screen, so the lanes of
+// a wavefront tend to hit the same few tiles.  Counting and filling are
+// aggregated per wavefront: one atomic per distinct tile and wave, the lanes
+// that share the tile take consecutive slots (ballot + popcount).
 // ---------------------------------------------------------------------------
-__global__ void k_setup_count(const float4 *__restrict__ pos_clip, const int32_t *__restrict__ tris,
-                              int B, int V, int T, int H, int W, int cull, int margin, int ntx,
-                              int nt, TriSetup *__restrict__ setup, int32_t *__restrict__ tile_count) {
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
+
+// next tile of a lane's tile rectangle in row-major order, -1 when done
+__device__ __forceinline__ int next_tile(int cur, int tx0, int tx1, int ty1, int ntx) {
+    int ty = cur / ntx, tx = cur - ty * ntx;
+    if (tx < tx1) return cur + 1;
+    if (ty < ty1) return (ty + 1) * ntx + tx0;
+    return -1;
+}
+
+// One pass: every triangle is set up and appended to the bins of the tiles
+// its box covers.  Each bin has a fixed capacity; its counter (kept at zero
+// between calls, reset by the rasterizer after reading it) gives the slot.
+__global__ void k_setup_bin(const float4 *__restrict__ pos_clip, const int32_t *__restrict__ tris,
+                            int B, int V, int T, int H, int W, int cull, int margin, int ntx, int nt,
+                            int cap, TriSetup *__restrict__ setup, int32_t *__restrict__ counts,
+                            int32_t *__restrict__ bins, unsigned long long *__restrict__ status) {
     int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid >= (int64_t)B * T) return;
-    int b = (int)(gid / T), t = (int)(gid - (int64_t)b * T);
-    const int32_t *tv = tris + 3 * (int64_t)t;
-    int v0 = tv[0], v1 = tv[1], v2 = tv[2];
-    TriSetup s;
-    if (v0 < 0 || v0 >= V || v1 < 0 || v1 >= V || v2 < 0 || v2 >= V) {
-        s.meta = 0;
-        s.box0 = s.box1 = 1;
-    } else {
-        s = dr_setup(pos_clip + (int64_t)b * V, v0, v1, v2, H, W, cull, margin);
-    }
-    setup[gid] = s;
-    if (!(s.meta & 1)) return;
-    int tx0 = (s.box0 & 0xffff) / DRESSI_TILE, tx1 = (s.box0 >> 16) / DRESSI_TILE;
-    int ty0 = (s.box1 & 0xffff) / DRESSI_TILE, ty1 = (s.box1 >> 16) / DRESSI_TILE;
-    int32_t *tc = tile_count + (int64_t)b * nt;
-    for (int ty = ty0; ty <= ty1; ty++)
-        for (int tx = tx0; tx <= tx1; tx++) atomicAdd(&tc[ty * ntx + tx], 1);
-}
-
-__global__ void k_fill_bins(const TriSetup *__restrict__ setup, int B, int T, int ntx, int nt,
-                            const int32_t *__restrict__ tile_off, int32_t *__restrict__ cursor,
-                            int32_t *__restrict__ bins, int64_t cap,
-                            unsigned long long *__restrict__ status) {
-    int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid == 0) {
-        int64_t total = tile_off[(int64_t)B * nt];
-        if (total > cap) {
-            atomicMax(&status[0], 1ull);
-            atomicMax(&status[1], (unsigned long long)total);
+    int cur = -1, tx0 = 0, tx1 = 0, ty1 = 0, b = 0, t = 0;
+    if (gid < (int64_t)B * T) {
+        b = (int)(gid / T);
+        t = (int)(gid - (int64_t)b * T);
+        const int32_t *tv = tris + 3 * (int64_t)t;
+        int v0 = tv[0], v1 = tv[1], v2 = tv[2];
+        TriSetup s;
+        if (v0 < 0 || v0 >= V || v1 < 0 || v1 >= V || v2 < 0 || v2 >= V) {
+            s.meta = 0;
+            s.box0 = s.box1 = 1;
+        } else {
+            s = dr_setup(pos_clip + (int64_t)b * V, v0, v1, v2, H, W, cull, margin);
+        }
+        setup[gid] = s;
+        if (s.meta & 1) {
+            tx0 = (s.box0 & 0xffff) / DRESSI_TILE;
+            tx1 = (s.box0 >> 16) / DRESSI_TILE;
+            int ty0 = (s.box1 & 0xffff) / DRESSI_TILE;
+            ty1 = (s.box1 >> 16) / DRESSI_TILE;
+            cur = ty0 * ntx + tx0;
         }
     }
-    if (gid >= (int64_t)B * T) return;
-    TriSetup s = setup[gid];
-    if (!(s.meta & 1)) return;
-    int b = (int)(gid / T), t = (int)(gid - (int64_t)b * T);
-    int tx0 = (s.box0 & 0xffff) / DRESSI_TILE, tx1 = (s.box0 >> 16) / DRESSI_TILE;
-    int ty0 = (s.box1 & 0xffff) / DRESSI_TILE, ty1 = (s.box1 >> 16) / DRESSI_TILE;
-    for (int ty = ty0; ty <= ty1; ty++)
-        for (int tx = tx0; tx <= tx1; tx++) {
-            int64_t bt = (int64_t)b * nt + ty * ntx + tx;
-            int64_t slot = (int64_t)tile_off[bt] + atomicAdd(&cursor[bt], 1);
-            if (slot < cap) bins[slot] = t;
+    // Rounds: in each round every lane with tiles left takes its next tile.
+    // Lanes are grouped by tile with ballots (ALU only), then every group's
+    // first lane issues one atomicAdd for the whole group - all groups in the
+    // same instruction - and the lanes take consecutive slots.
+    const unsigned long long below = (1ull << lane_id()) - 1ull;
+    int worst = 0;
+    unsigned long long active = __ballot(cur >= 0);
+    while (active) {
+        int leader = -1, rank = 0, gsize = 0;
+        unsigned long long todo = active;
+        while (todo) {
+            int src = __ffsll((long long)todo) - 1;
+            int key_tile = __shfl(cur, src, 64);
+            int key_b = __shfl(b, src, 64);
+            unsigned long long same = __ballot(cur >= 0 && cur == key_tile && b == key_b);
+            if ((same >> lane_id()) & 1ull) {
+                leader = src;
+                rank = __popcll(same & below);
+                gsize = __popcll(same);
+            }
+            todo &= ~same;
         }
+        int base = 0;
+        if (cur >= 0 && leader == lane_id())
+            base = atomicAdd(&counts[(int64_t)b * nt + cur], gsize);
+        base = __shfl(base, leader < 0 ? 0 : leader, 64);
+        if (cur >= 0) {
+            int64_t bt = (int64_t)b * nt + cur;
+            int slot = base + rank;
+            if (slot < cap) bins[bt * cap + slot] = t;
+            else worst = max(worst, slot + 1);
+            cur = next_tile(cur, tx0, tx1, ty1, ntx);
+        }
+        active = __ballot(cur >= 0);
+    }
+    if (worst > 0) {
+        atomicMax(&status[0], 1ull);
+        atomicMax(&status[1], (unsigned long long)worst);
+    }
 }
 
 // ---------------------------------------------------------------------------
-// tile rasterizer
+// fine rasterizer: one 16x16 tile per workgroup; each lane takes one binned
+// triangle and walks the pixels of its box inside the tile, merging fragment
+// keys into a per-pixel LDS slot with a 64-bit atomicMin of
+// (key bits << 32 | triangle id).  Keys are positive floats, whose bit
+// patterns order like the values, so the slot ends as the smallest key and the
+// smallest id at that key, independently of the visiting order.  Layer k > 0
+// repeats the pass keeping only keys strictly above the pixel's layer k-1 key
+// (depth peeling, PeelDepth's "discard if key <= previous").
 // ---------------------------------------------------------------------------
-template <int K>
-__device__ __forceinline__ void klist_insert(float (&key)[K], int (&id)[K], float k, int t) {
-    bool dup = false;
-#pragma unroll
-    for (int j = 0; j < K; j++)
-        if (key[j] == k) {
-            dup = true;
-            id[j] = min(id[j], t);
-        }
-    if (dup || !(k < key[K - 1])) return;
-    float ck = k;
-    int ct = t;
-#pragma unroll
-    for (int j = 0; j < K; j++) {
-        if (ck < key[j]) {
-            float tk = key[j];
-            int ti = id[j];
-            key[j] = ck;
-            id[j] = ct;
-            ck = tk;
-            ct = ti;
-        }
-    }
-}
+#define RS_EMPTY 0xffffffffffffffffull
 
-template <int K, bool SOFT>
-__global__ void __launch_bounds__(DRESSI_TILE_PIX)
-    k_raster(const TriSetup *__restrict__ setup, const int32_t *__restrict__ tile_off,
-             const int32_t *__restrict__ bins, int64_t cap, int T, int H, int W, int ntx, int nt,
-             float r, int32_t *__restrict__ tri_id, float2 *__restrict__ bary,
-             float *__restrict__ dist) {
-    __shared__ TriSetup sh[DRESSI_TILE_PIX];
-    __shared__ int shid[DRESSI_TILE_PIX];
-    const int bt = blockIdx.x;
-    const int b = bt / nt, tile = bt - b * nt;
-    const int tx = tile % ntx, ty = tile / ntx;
-    const int x = tx * DRESSI_TILE + (threadIdx.x & (DRESSI_TILE - 1));
-    const int y = ty * DRESSI_TILE + (threadIdx.x / DRESSI_TILE);
-    const int px = DRESSI_SUBPIX * x + DRESSI_SUBPIX / 2;
-    const int py = DRESSI_SUBPIX * y + DRESSI_SUBPIX / 2;
-    const float dscale = (float)W * 256.0f;
-    const TriSetup *sv = setup + (int64_t)b * T;
-
-    float key[K];
-    int id[K];
-#pragma unroll
-    for (int k = 0; k < K; k++) {
-        key[k] = FLT_MAX;
-        id[k] = -1;
-    }
-    int64_t beg = tile_off[bt];
-    int64_t end = tile_off[bt + 1];
-    if (end > cap) end = cap;
-    for (int64_t c0 = beg; c0 < end; c0 += DRESSI_TILE_PIX) {
-        int n = (end - c0 < DRESSI_TILE_PIX) ? (int)(end - c0) : DRESSI_TILE_PIX;
-        __syncthreads();
-        if ((int)threadIdx.x < n) {
-            int t = bins[c0 + threadIdx.x];
-            shid[threadIdx.x] = t;
-            sh[threadIdx.x] = sv[t];
-        }
-        __syncthreads();
-        for (int j = 0; j < n; j++) {
-            const TriSetup &s = sh[j];
-            int bx0 = s.box0 & 0xffff, bx1 = s.box0 >> 16;
-            int by0 = s.box1 & 0xffff, by1 = s.box1 >> 16;
-            if (x < bx0 || x > bx1 || y < by0 || y > by1) continue;
+template <bool SOFT>
+__device__ __forceinline__ void raster_tri_in_tile(const TriSetup &s, int t, int tx, int ty,
+                                                   float r, float dscale,
+                                                   unsigned long long *slot, const float *prev) {
+    int x0 = max(s.box0 & 0xffff, tx * DRESSI_TILE), x1 = min(s.box0 >> 16, tx * DRESSI_TILE + DRESSI_TILE - 1);
+    int y0 = max(s.box1 & 0xffff, ty * DRESSI_TILE), y1 = min(s.box1 >> 16, ty * DRESSI_TILE + DRESSI_TILE - 1);
+    for (int y = y0; y <= y1; y++) {
+        const int py = DRESSI_SUBPIX * y + DRESSI_SUBPIX / 2;
+        for (int x = x0; x <= x1; x++) {
+            const int px = DRESSI_SUBPIX * x + DRESSI_SUBPIX / 2;
             int64_t E[3];
             bool in = true;
 #pragma unroll
@@ -149,19 +138,76 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX)
                 bool own = (s.meta >> (1 + i)) & 1;
                 in = in && (E[i] > 0 || (E[i] == 0 && own));
             }
+            float key;
             if (in) {
                 float z = dr_depth(s, E);
-                if (z > 0.0f && z < 1.0f) klist_insert<K>(key, id, 0.5f * z, shid[j]);
-            } else if (SOFT) {
+                if (!(z > 0.0f && z < 1.0f)) continue;
+                key = 0.5f * z;
+            } else {
+                if (!SOFT) continue;
                 int ne;
                 float dn = dr_distnorm(s.X, s.Y, px, py, E, dscale, ne);
-                if (dn <= r) {
-                    float h = 0.5f * dn;
-                    klist_insert<K>(key, id, h + 0.5f, shid[j]);
-                }
+                if (!(dn <= r)) continue;
+                float h = 0.5f * dn;
+                key = h + 0.5f;
             }
+            int p = (y - ty * DRESSI_TILE) * DRESSI_TILE + (x - tx * DRESSI_TILE);
+            if (!(key > prev[p])) continue;
+            unsigned long long v = ((unsigned long long)__float_as_uint(key) << 32) | (unsigned)t;
+            atomicMin(&slot[p], v);
         }
     }
+}
+
+template <int K, bool SOFT>
+__global__ void __launch_bounds__(DRESSI_TILE_PIX)
+    k_raster(const TriSetup *__restrict__ setup, int32_t *__restrict__ counts,
+             const int32_t *__restrict__ bins, int cap, int T, int H, int W, int ntx, int nt,
+             float r, int32_t *__restrict__ tri_id, float2 *__restrict__ bary,
+             float *__restrict__ dist) {
+    __shared__ unsigned long long slot[DRESSI_TILE_PIX];
+    __shared__ float prev[DRESSI_TILE_PIX];
+    const int bt = blockIdx.x;
+    const int b = bt / nt, tile = bt - b * nt;
+    const int tx = tile % ntx, ty = tile / ntx;
+    const int p = threadIdx.x;
+    const int x = tx * DRESSI_TILE + (p & (DRESSI_TILE - 1));
+    const int y = ty * DRESSI_TILE + (p / DRESSI_TILE);
+    const int px = DRESSI_SUBPIX * x + DRESSI_SUBPIX / 2;
+    const int py = DRESSI_SUBPIX * y + DRESSI_SUBPIX / 2;
+    const float dscale = (float)W * 256.0f;
+    const TriSetup *sv = setup + (int64_t)b * T;
+    const int32_t *bin = bins + (int64_t)bt * cap;
+    int nbin = counts[bt];
+    if (nbin > cap) nbin = cap;
+
+    float key[K];
+    int id[K];
+    prev[p] = 0.0f;
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+        slot[p] = RS_EMPTY;
+        __syncthreads();
+        for (int c0 = 0; c0 < nbin; c0 += DRESSI_TILE_PIX) {
+            if (c0 + p < nbin) {
+                int t = bin[c0 + p];
+                TriSetup s = sv[t];
+                raster_tri_in_tile<SOFT>(s, t, tx, ty, r, dscale, slot, prev);
+            }
+        }
+        __syncthreads();
+        unsigned long long v = slot[p];
+        if (v == RS_EMPTY) {
+            key[k] = 2.0f;
+            id[k] = -1;
+        } else {
+            key[k] = __uint_as_float((unsigned)(v >> 32));
+            id[k] = (int)(v & 0xffffffffu);
+        }
+        prev[p] = key[k];   // an empty layer (2.0) blocks every later key
+        __syncthreads();
+    }
+    if (p == 0) counts[bt] = 0;   // every lane has read it before the first barrier
     if (x >= W || y >= H) return;
 #pragma unroll
     for (int k = 0; k < K; k++) {
@@ -197,16 +243,15 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX)
 }
 
 template <int K>
-static void launch_raster_k(bool soft, dim3 g, hipStream_t st, const TriSetup *setup,
-                            const int32_t *off, const int32_t *bins, int64_t cap, int T, int H,
-                            int W, int ntx, int nt, float r, int32_t *tid, float2 *bary,
-                            float *dist) {
+static void launch_raster_k(bool soft, dim3 g, hipStream_t st, const TriSetup *setup, int32_t *counts,
+                            const int32_t *bins, int cap, int T, int H, int W, int ntx, int nt, float r,
+                            int32_t *tid, float2 *bary, float *dist) {
     if (soft)
-        DR_LAUNCH("k_raster", (k_raster<K, true>), g, DRESSI_TILE_PIX, 0, st, setup, off, bins, cap, T, H, W, ntx, nt, r,
-                                                         tid, bary, dist);
+        DR_LAUNCH("k_raster", (k_raster<K, true>), g, DRESSI_TILE_PIX, 0, st, setup, counts, bins, cap, T, H,
+                  W, ntx, nt, r, tid, bary, dist);
     else
-        DR_LAUNCH("k_raster", (k_raster<K, false>), g, DRESSI_TILE_PIX, 0, st, setup, off, bins, cap, T, H, W, ntx, nt,
-                                                          r, tid, bary, dist);
+        DR_LAUNCH("k_raster", (k_raster<K, false>), g, DRESSI_TILE_PIX, 0, st, setup, counts, bins, cap, T, H,
+                  W, ntx, nt, r, tid, bary, dist);
 }
 
 static int soft_margin(float r, int W) {
@@ -214,19 +259,24 @@ static int soft_margin(float r, int W) {
     return (int)ceilf(r * (float)W) + 1;
 }
 
-static int64_t default_bin_capacity(int B, int T, int nt, int margin) {
-    int64_t per = 4 + 2 * (int64_t)((margin + DRESSI_TILE - 1) / DRESSI_TILE);
-    int64_t cap = (int64_t)B * T * per * per / 4 + (int64_t)B * nt + 4096;
+// triangles per tile bin: 8x the mean load of a covered tile, at least 2048
+static int default_tile_capacity(int B, int T, int nt, int margin) {
+    double side = 1.0 + (2.0 * margin + 2.0) / DRESSI_TILE;
+    double mean = (double)T * side * side / (nt > 0 ? nt : 1);
+    int cap = 2048;
+    while (cap < 8.0 * mean && cap < (1 << 24)) cap <<= 1;
     return cap;
 }
 
-static size_t raster_scratch(int B, int T, int nt, int64_t cap, Carver &c, size_t *o) {
+static int tile_capacity(const dressi_ctx *ctx, int B, int T, int nt, int margin) {
+    int cap = default_tile_capacity(B, T, nt, margin);
+    if (ctx && ctx->bin_capacity > cap) cap = (int)std::min<int64_t>(ctx->bin_capacity, 1 << 26);
+    return cap;
+}
+
+static size_t raster_scratch(int B, int T, int nt, int cap, Carver &c, size_t *o) {
     o[0] = c.take(sizeof(TriSetup) * (size_t)B * T);            // setup
-    o[1] = c.take(sizeof(int32_t) * (size_t)B * nt);            // counts
-    o[2] = c.take(sizeof(int32_t) * ((size_t)B * nt + 1));      // offsets
-    o[3] = c.take(sizeof(int32_t) * (size_t)B * nt);            // cursor
-    o[4] = c.take(dressi_scan_tmp_bytes((int64_t)B * nt));      // scan tmp
-    o[5] = c.take(sizeof(int32_t) * (size_t)cap);               // bins
+    o[1] = c.take(sizeof(int32_t) * (size_t)B * nt * cap);      // bins
     return c.off;
 }
 
@@ -255,39 +305,31 @@ extern "C" int dressi_rasterize(dressi_ctx *ctx, const float *pos_clip, const in
     hipStream_t st = (hipStream_t)stream;
     int ntx = tiles_x(W), nty = tiles_y(H), nt = ntx * nty;
     int margin = soft_margin(r, W);
-    int64_t cap = ctx->bin_capacity;
-    int64_t dflt = default_bin_capacity(B, T, nt, margin);
-    if (cap < dflt) cap = dflt;
+    int cap = tile_capacity(ctx, B, T, nt, margin);
     Carver c;
-    size_t o[6];
+    size_t o[2];
     raster_scratch(B, T, nt, cap, c, o);
     rc = dressi_scratch(ctx, c.off, st);
     if (rc) return rc;
+    rc = dressi_counters(ctx, (size_t)B * nt, st);
+    if (rc) return rc;
     void *S = ctx->scratch;
     TriSetup *setup = at<TriSetup>(S, o[0]);
-    int32_t *counts = at<int32_t>(S, o[1]);
-    int32_t *offs = at<int32_t>(S, o[2]);
-    int32_t *cursor = at<int32_t>(S, o[3]);
-    int32_t *bins = at<int32_t>(S, o[5]);
+    int32_t *bins = at<int32_t>(S, o[1]);
+    int32_t *counts = ctx->counters;
     int64_t ntri = (int64_t)B * T;
-    dressi_fill_i32(counts, 0, (int64_t)B * nt, st);
-    dressi_fill_i32(cursor, 0, (int64_t)B * nt, st);
     if (ntri > 0)
-        DR_LAUNCH("k_setup_count", (k_setup_count), (int)((ntri + 255) / 256), 256, 0, st, 
-            reinterpret_cast<const float4 *>(pos_clip), tris, B, V, T, H, W, cull, margin, ntx, nt,
-            setup, counts);
-    dressi_exclusive_scan(counts, offs, (int64_t)B * nt, at<void>(S, o[4]), st);
-    DR_LAUNCH("k_fill_bins", (k_fill_bins), (int)((ntri + 255) / 256 + 1), 256, 0, st, 
-        setup, B, T, ntx, nt, offs, cursor, bins, cap,
-        reinterpret_cast<unsigned long long *>(ctx->status));
+        DR_LAUNCH("k_setup_bin", (k_setup_bin), (int)((ntri + 255) / 256), 256, 0, st,
+                  reinterpret_cast<const float4 *>(pos_clip), tris, B, V, T, H, W, cull, margin, ntx, nt,
+                  cap, setup, counts, bins, reinterpret_cast<unsigned long long *>(ctx->status));
     dim3 g((unsigned)(B * nt));
     float2 *b2 = reinterpret_cast<float2 *>(bary);
     switch (K) {
-    case 1: launch_raster_k<1>(soft, g, st, setup, offs, bins, cap, T, H, W, ntx, nt, r, tri_id, b2, dist); break;
-    case 2: launch_raster_k<2>(soft, g, st, setup, offs, bins, cap, T, H, W, ntx, nt, r, tri_id, b2, dist); break;
-    case 3: launch_raster_k<3>(soft, g, st, setup, offs, bins, cap, T, H, W, ntx, nt, r, tri_id, b2, dist); break;
-    case 4: launch_raster_k<4>(soft, g, st, setup, offs, bins, cap, T, H, W, ntx, nt, r, tri_id, b2, dist); break;
-    default: launch_raster_k<5>(soft, g, st, setup, offs, bins, cap, T, H, W, ntx, nt, r, tri_id, b2, dist); break;
+    case 1: launch_raster_k<1>(soft, g, st, setup, counts, bins, cap, T, H, W, ntx, nt, r, tri_id, b2, dist); break;
+    case 2: launch_raster_k<2>(soft, g, st, setup, counts, bins, cap, T, H, W, ntx, nt, r, tri_id, b2, dist); break;
+    case 3: launch_raster_k<3>(soft, g, st, setup, counts, bins, cap, T, H, W, ntx, nt, r, tri_id, b2, dist); break;
+    case 4: launch_raster_k<4>(soft, g, st, setup, counts, bins, cap, T, H, W, ntx, nt, r, tri_id, b2, dist); break;
+    default: launch_raster_k<5>(soft, g, st, setup, counts, bins, cap, T, H, W, ntx, nt, r, tri_id, b2, dist); break;
     }
     return dressi_launch_check(ctx, "rasterize");
 }
@@ -299,9 +341,10 @@ extern "C" int dressi_rasterize(dressi_ctx *ctx, const float *pos_clip, const in
 #define FS_SENT 0xffffffffu
 
 __global__ void __launch_bounds__(DRESSI_TILE_PIX)
-    k_fragsort(const int32_t *__restrict__ tri_id, int K, int H, int W, int ntx, int nt, int np,
+    k_fragsort(const int32_t *__restrict__ tri_id, int K, int H, int W, int ntx, int nt, int np, int T,
                int32_t *__restrict__ n_frag, int32_t *__restrict__ n_rec, uint16_t *__restrict__ frag,
-               int32_t *__restrict__ rec_tri, int32_t *__restrict__ rec_start) {
+               int32_t *__restrict__ rec_tri, int32_t *__restrict__ rec_start,
+               int32_t *__restrict__ tri_counts) {
     __shared__ uint32_t keys[FS_MAXN];
     __shared__ int wsum[DRESSI_TILE_PIX / 64];
     const int bt = blockIdx.x;
@@ -381,8 +424,10 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX)
         if (kv == FS_SENT) break;
         frag[base + i] = (uint16_t)(kv & 2047u);
         if (i == 0 || (keys[i - 1] >> 11) != (kv >> 11)) {
-            rec_tri[base + r] = (int32_t)(kv >> 11);
+            int t = (int)(kv >> 11);
+            rec_tri[base + r] = t;
             rec_start[base + r] = i;
+            if (t < T) atomicAdd(&tri_counts[(int64_t)b * T + t], 1);
             r++;
         }
     }
@@ -396,51 +441,43 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX)
     if (p == 0) n_rec[bt] = total_heads;
 }
 
-size_t dressi_fraglists_bytes(int B, int H, int W, int K) {
+static void fragindex_layout(int B, int K, int H, int W, int T, Carver &c, size_t *o) {
     int64_t nt = (int64_t)tiles_x(W) * tiles_y(H);
     int64_t n = (int64_t)B * nt * DRESSI_TILE_PIX * K;
+    o[0] = c.take(sizeof(int32_t) * B * nt);                 // n_frag
+    o[1] = c.take(sizeof(int32_t) * B * nt);                 // n_rec
+    o[2] = c.take(sizeof(uint16_t) * n);                     // frag
+    o[3] = c.take(sizeof(int32_t) * n);                      // rec_tri
+    o[4] = c.take(sizeof(int32_t) * n);                      // rec_start
+    o[5] = c.take(sizeof(int32_t) * ((int64_t)B * T + 1));   // triangle -> tiles offsets
+    o[6] = c.take(sizeof(int2) * n);                         // triangle -> tiles entries
+}
+
+size_t dressi_fragindex_bytes(int B, int K, int H, int W, int T) {
     Carver c;
-    c.take(sizeof(int32_t) * B * nt);
-    c.take(sizeof(int32_t) * B * nt);
-    c.take(sizeof(uint16_t) * n);
-    c.take(sizeof(int32_t) * n);
-    c.take(sizeof(int32_t) * n);
+    size_t o[7];
+    fragindex_layout(B, K, H, W, T, c, o);
     return c.off;
 }
 
-void dressi_build_fraglists(const int32_t *tri_id, int B, int K, int H, int W, void *scratch,
-                            FragLists &fl, hipStream_t s) {
-    int ntx = tiles_x(W), nt = ntx * tiles_y(H);
-    int64_t n = (int64_t)B * nt * DRESSI_TILE_PIX * K;
+void dressi_fragindex_view(void *base, int B, int K, int H, int W, int T, FragLists &fl, TriTiles &tt) {
     Carver c;
-    fl.n_frag = at<int32_t>(scratch, c.take(sizeof(int32_t) * B * nt));
-    fl.n_rec = at<int32_t>(scratch, c.take(sizeof(int32_t) * B * nt));
-    fl.frag = at<uint16_t>(scratch, c.take(sizeof(uint16_t) * n));
-    fl.rec_tri = at<int32_t>(scratch, c.take(sizeof(int32_t) * n));
-    fl.rec_start = at<int32_t>(scratch, c.take(sizeof(int32_t) * n));
-    int np = 256;
-    while (np < DRESSI_TILE_PIX * K) np <<= 1;
-    if (B * nt > 0)
-        DR_LAUNCH("k_fragsort", (k_fragsort), B * nt, DRESSI_TILE_PIX, 0, s, tri_id, K, H, W, ntx, nt, np, fl.n_frag,
-                                                       fl.n_rec, fl.frag, fl.rec_tri, fl.rec_start);
+    size_t o[7];
+    fragindex_layout(B, K, H, W, T, c, o);
+    fl.n_frag = at<int32_t>(base, o[0]);
+    fl.n_rec = at<int32_t>(base, o[1]);
+    fl.frag = at<uint16_t>(base, o[2]);
+    fl.rec_tri = at<int32_t>(base, o[3]);
+    fl.rec_start = at<int32_t>(base, o[4]);
+    tt.offsets = at<int32_t>(base, o[5]);
+    tt.entries = at<int2>(base, o[6]);
 }
 
 // ---------------------------------------------------------------------------
 // triangle -> tiles transpose of the per-tile records
 // ---------------------------------------------------------------------------
-__global__ void k_tt_count(FragLists fl, int K, int T, int nt, int32_t *__restrict__ counts) {
-    const int bt = blockIdx.x;
-    const int b = bt / nt;
-    const int64_t base = (int64_t)bt * DRESSI_TILE_PIX * K;
-    const int n = fl.n_rec[bt];
-    for (int r = threadIdx.x; r < n; r += blockDim.x) {
-        int t = fl.rec_tri[base + r];
-        if (t >= 0 && t < T) atomicAdd(&counts[(int64_t)b * T + t], 1);
-    }
-}
-
 __global__ void k_tt_fill(FragLists fl, int K, int T, int nt, const int32_t *__restrict__ offsets,
-                          int32_t *__restrict__ cursor, int2 *__restrict__ entries) {
+                          int32_t *__restrict__ counts, int2 *__restrict__ entries) {
     const int bt = blockIdx.x;
     const int b = bt / nt;
     const int64_t base = (int64_t)bt * DRESSI_TILE_PIX * K;
@@ -449,7 +486,8 @@ __global__ void k_tt_fill(FragLists fl, int K, int T, int nt, const int32_t *__r
         int t = fl.rec_tri[base + r];
         if (t < 0 || t >= T) continue;
         int64_t bt_t = (int64_t)b * T + t;
-        int slot = offsets[bt_t] + atomicAdd(&cursor[bt_t], 1);
+        // counting back down leaves the counters at zero for the next call
+        int slot = offsets[bt_t] + atomicSub(&counts[bt_t], 1) - 1;
         entries[slot] = make_int2(bt, r);
     }
 }
@@ -470,34 +508,46 @@ __global__ void k_tt_sort(const int32_t *__restrict__ offsets, int2 *__restrict_
     }
 }
 
-size_t dressi_tritiles_bytes(int B, int T, int H, int W, int K) {
-    int64_t nt = (int64_t)tiles_x(W) * tiles_y(H);
+size_t dressi_fragindex_tmp_bytes(int B, int T) { return dressi_scan_tmp_bytes((int64_t)B * T); }
+
+// counts: B*T zero counters (left at zero)
+void dressi_build_fragindex(const int32_t *tri_id, int B, int K, int H, int W, int T, void *base,
+                            void *tmp, int32_t *counts, hipStream_t s) {
+    FragLists fl;
+    TriTiles tt;
+    dressi_fragindex_view(base, B, K, H, W, T, fl, tt);
+    int ntx = tiles_x(W), nt = ntx * tiles_y(H);
+    int np = 256;
+    while (np < DRESSI_TILE_PIX * K) np <<= 1;
+    if (B * nt > 0)
+        DR_LAUNCH("k_fragsort", (k_fragsort), B * nt, DRESSI_TILE_PIX, 0, s, tri_id, K, H, W, ntx, nt, np, T,
+                  fl.n_frag, fl.n_rec, fl.frag, fl.rec_tri, fl.rec_start, counts);
     int64_t n = (int64_t)B * T;
-    Carver c;
-    c.take(sizeof(int32_t) * (n + 1));
-    c.take(sizeof(int2) * (size_t)B * nt * DRESSI_TILE_PIX * K);
-    c.take(sizeof(int32_t) * n);
-    c.take(sizeof(int32_t) * n);
-    c.take(dressi_scan_tmp_bytes(n));
-    return c.off;
+    dressi_exclusive_scan(counts, tt.offsets, n, tmp, s);
+    if (B * nt > 0)
+        DR_LAUNCH("k_tt_fill", (k_tt_fill), B * nt, 256, 0, s, fl, K, T, nt, tt.offsets, counts, tt.entries);
+    if (n > 0) DR_LAUNCH("k_tt_sort", (k_tt_sort), (int)((n + 255) / 256), 256, 0, s, tt.offsets, tt.entries, n);
 }
 
-void dressi_build_tritiles(const FragLists &fl, int B, int T, int K, int H, int W, void *scratch,
-                           TriTiles &tt, hipStream_t s) {
-    int nt = tiles_x(W) * tiles_y(H);
-    int64_t n = (int64_t)B * T;
-    Carver c;
-    tt.offsets = at<int32_t>(scratch, c.take(sizeof(int32_t) * (n + 1)));
-    tt.entries = at<int2>(scratch, c.take(sizeof(int2) * (size_t)B * nt * DRESSI_TILE_PIX * K));
-    int32_t *counts = at<int32_t>(scratch, c.take(sizeof(int32_t) * n));
-    int32_t *cursor = at<int32_t>(scratch, c.take(sizeof(int32_t) * n));
-    void *tmp = at<void>(scratch, c.take(dressi_scan_tmp_bytes(n)));
-    dressi_fill_i32(counts, 0, n, s);
-    dressi_fill_i32(cursor, 0, n, s);
-    if (B * nt > 0) DR_LAUNCH("k_tt_count", (k_tt_count), B * nt, 256, 0, s, fl, K, T, nt, counts);
-    dressi_exclusive_scan(counts, tt.offsets, n, tmp, s);
-    if (B * nt > 0) DR_LAUNCH("k_tt_fill", (k_tt_fill), B * nt, 256, 0, s, fl, K, T, nt, tt.offsets, cursor, tt.entries);
-    if (n > 0) DR_LAUNCH("k_tt_sort", (k_tt_sort), (int)((n + 255) / 256), 256, 0, s, tt.offsets, tt.entries, n);
+extern "C" size_t dressi_fragment_index_bytes(int B, int K, int H, int W, int T) {
+    if (B < 0 || K < 1 || K > DRESSI_MAX_K || H < 0 || W < 0 || T < 0) return 0;
+    return dressi_fragindex_bytes(B, K, H, W, T);
+}
+
+extern "C" int dressi_fragment_index(dressi_ctx *ctx, const int32_t *tri_id, int B, int K, int H, int W,
+                                     int T, void *index, void *stream) {
+    if (!ctx) return DRESSI_EINVAL;
+    if (B < 0 || K < 1 || K > DRESSI_MAX_K || H < 0 || W < 0 || T < 0)
+        return dressi_fail(ctx, DRESSI_EINVAL, "fragment_index: bad dimensions");
+    if (!index || ((int64_t)B * H * W > 0 && !tri_id))
+        return dressi_fail(ctx, DRESSI_EINVAL, "fragment_index: null pointer");
+    hipStream_t st = (hipStream_t)stream;
+    int rc = dressi_scratch(ctx, dressi_fragindex_tmp_bytes(B, T), st);
+    if (rc) return rc;
+    rc = dressi_counters(ctx, (size_t)B * T, st);
+    if (rc) return rc;
+    dressi_build_fragindex(tri_id, B, K, H, W, T, index, ctx->scratch, ctx->counters, st);
+    return dressi_launch_check(ctx, "fragment_index");
 }
 
 // binary search of triangle t among the sorted records of one tile; returns
@@ -520,131 +570,178 @@ __device__ __forceinline__ void frag_range(const FragLists &fl, int64_t bt, int6
 
 // ---------------------------------------------------------------------------
 // rasterization backward
+//
+// 1. per tile: every fragment's gradient w.r.t. the screen positions (and the
+//    direct w term) of its triangle's three corners, kept in LDS; the tile's
+//    fragments are already sorted by triangle, so each triangle's fragments are
+//    summed in that order into one record (a segmented sum);
+// 2. per (view, triangle): its records summed in tile order, then mapped from
+//    screen to clip space;
+// 3. per (view, vertex): its corners summed in ascending order.
 // ---------------------------------------------------------------------------
-__global__ void k_rast_bwd_tri(const float4 *__restrict__ pos_clip, const int32_t *__restrict__ tris,
-                               int B, int V, int T, int H, int W, int K, int cull, int margin,
-                               int ntx, int nt, FragLists fl, const float2 *__restrict__ grad_bary,
-                               const float *__restrict__ grad_dist, float *__restrict__ corner_grad) {
-    int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid >= (int64_t)B * T) return;
-    int b = (int)(gid / T), t = (int)(gid - (int64_t)b * T);
-    float *cg = corner_grad + gid * 9;
-    const int32_t *tv = tris + 3 * (int64_t)t;
-    int vid[3] = {tv[0], tv[1], tv[2]};
-    bool ok = vid[0] >= 0 && vid[0] < V && vid[1] >= 0 && vid[1] < V && vid[2] >= 0 && vid[2] < V;
-    TriSetup s;
-    if (ok) s = dr_setup(pos_clip + (int64_t)b * V, vid[0], vid[1], vid[2], H, W, cull, margin);
-    if (!ok || !(s.meta & 1)) {
-#pragma unroll
-        for (int i = 0; i < 9; i++) cg[i] = 0.0f;
-        return;
-    }
-    float sx[3], sy[3];
+
+// gradient of one fragment: out[corner*3 + {0,1,2}] = d/dx_screen, d/dy_screen,
+// d/dw (direct) of that corner, original corner order
+__device__ __forceinline__ void rast_frag_grad(const TriSetup &s, int x, int y, float2 g2, float gdist,
+                                               bool want_dist, int W, float *out) {
+    const int px = DRESSI_SUBPIX * x + DRESSI_SUBPIX / 2, py = DRESSI_SUBPIX * y + DRESSI_SUBPIX / 2;
+    int64_t E[3];
+    bool in = true;
 #pragma unroll
     for (int i = 0; i < 3; i++) {
-        sx[i] = (float)s.X[i] * (1.0f / 256.0f);
-        sy[i] = (float)s.Y[i] * (1.0f / 256.0f);
+        E[i] = dr_edge(s.X, s.Y, i, px, py);
+        bool own = (s.meta >> (1 + i)) & 1;
+        in = in && (E[i] > 0 || (E[i] == 0 && own));
     }
+    const bool swapped = dr_corner(s.meta, 1) == 2;
+    // the barycentric chain runs in double (see the forward)
     const double A2d = (double)s.Af;
     const double A = A2d * (1.0 / 65536.0);
-    // grad_p lambda_i (pixel units), edge i from a = i+1 to c = i+2
-    double glx[3], gly[3];
+    double l[3], q[3];
+#pragma unroll
+    for (int i = 0; i < 3; i++) {
+        l[i] = (double)E[i] / A2d;
+        q[i] = l[i] / (double)s.w[i];
+    }
+    double Q = q[0] + q[1] + q[2];
+    // gradient on the normalised-order barycentrics (original corner 2 has none)
+    double gb[3] = {g2.x, swapped ? 0.0 : (double)g2.y, swapped ? (double)g2.y : 0.0};
+    double sb = (gb[0] * q[0] + gb[1] * q[1] + gb[2] * q[2]) / Q;
+    double Gx = 0.0, Gy = 0.0, gw[3];
 #pragma unroll
     for (int i = 0; i < 3; i++) {
         int a = (i + 1) % 3, c = (i + 2) % 3;
-        glx[i] = -((double)s.Y[c] - (double)s.Y[a]) * (1.0 / 256.0) / A;
-        gly[i] = ((double)s.X[c] - (double)s.X[a]) * (1.0 / 256.0) / A;
+        double wi = (double)s.w[i];
+        double gq = (gb[i] - sb) / Q;
+        double gl = gq / wi;
+        gw[i] = -gq * l[i] / (wi * wi);
+        Gx += gl * (-((double)s.Y[c] - (double)s.Y[a]) * (1.0 / 256.0) / A);
+        Gy += gl * (((double)s.X[c] - (double)s.X[a]) * (1.0 / 256.0) / A);
     }
-    const bool swapped = dr_corner(s.meta, 1) == 2;
-    const float dscale = (float)W * 256.0f;
-    const float invW = 1.0f / (float)W;
-    double gsx[3] = {0, 0, 0}, gsy[3] = {0, 0, 0}, gw[3] = {0, 0, 0};
-    int tx0 = (s.box0 & 0xffff) / DRESSI_TILE, tx1 = (s.box0 >> 16) / DRESSI_TILE;
-    int ty0 = (s.box1 & 0xffff) / DRESSI_TILE, ty1 = (s.box1 >> 16) / DRESSI_TILE;
-    for (int ty = ty0; ty <= ty1; ty++)
-        for (int tx = tx0; tx <= tx1; tx++) {
-            int64_t bt = (int64_t)b * nt + ty * ntx + tx;
-            int64_t base = bt * DRESSI_TILE_PIX * K;
-            int j0, j1;
-            frag_range(fl, bt, base, t, j0, j1);
-            for (int j = j0; j < j1; j++) {
-                int f = fl.frag[base + j];
-                int k = f >> 8, pl = f & 255;
-                int x = tx * DRESSI_TILE + (pl & 15), y = ty * DRESSI_TILE + (pl >> 4);
-                int64_t o = (((int64_t)b * K + k) * H + y) * W + x;
-                int px = DRESSI_SUBPIX * x + DRESSI_SUBPIX / 2, py = DRESSI_SUBPIX * y + DRESSI_SUBPIX / 2;
-                int64_t E[3];
-                bool in = true;
+    float gsx[3], gsy[3];
 #pragma unroll
-                for (int i = 0; i < 3; i++) {
-                    E[i] = dr_edge(s.X, s.Y, i, px, py);
-                    bool own = (s.meta >> (1 + i)) & 1;
-                    in = in && (E[i] > 0 || (E[i] == 0 && own));
-                }
-                // the barycentric chain runs in double (see the forward)
-                double l[3], q[3];
-#pragma unroll
-                for (int i = 0; i < 3; i++) {
-                    l[i] = (double)E[i] / A2d;
-                    q[i] = l[i] / (double)s.w[i];
-                }
-                double Q = q[0] + q[1] + q[2];
-                float2 g2 = grad_bary[o];
-                // gradient on the normalised-order barycentrics (original corner 2 has none)
-                double gb[3] = {g2.x, swapped ? 0.0 : (double)g2.y, swapped ? (double)g2.y : 0.0};
-                double sb = (gb[0] * q[0] + gb[1] * q[1] + gb[2] * q[2]) / Q;
-                double Gx = 0.0, Gy = 0.0;
-#pragma unroll
-                for (int i = 0; i < 3; i++) {
-                    double wi = (double)s.w[i];
-                    double gq = (gb[i] - sb) / Q;
-                    double gl = gq / wi;
-                    gw[i] -= gq * l[i] / (wi * wi);
-                    Gx += gl * glx[i];
-                    Gy += gl * gly[i];
-                }
-#pragma unroll
-                for (int i = 0; i < 3; i++) {
-                    gsx[i] -= l[i] * Gx;
-                    gsy[i] -= l[i] * Gy;
-                }
-                if (grad_dist) {
-                    float g = grad_dist[o];
-                    int ne;
-                    dr_distnorm(s.X, s.Y, px, py, E, dscale, ne);
-                    int a = (ne + 1) % 3, c = (ne + 2) % 3;
-                    float Px = (float)x + 0.5f, Py = (float)y + 0.5f;
-                    float ex = sx[c] - sx[a], ey = sy[c] - sy[a];
-                    float tt = ((Px - sx[a]) * ex + (Py - sy[a]) * ey) / (ex * ex + ey * ey);
-                    tt = fminf(fmaxf(tt, 0.0f), 1.0f);
-                    float cx = sx[a] + tt * ex, cy = sy[a] + tt * ey;
-                    float dx = Px - cx, dy = Py - cy;
-                    float d = sqrtf(dx * dx + dy * dy);
-                    if (d > 0.0f && g != 0.0f) {
-                        float sg = (in ? g : -g) * invW / d;
-                        gsx[a] -= sg * (1.0f - tt) * dx;
-                        gsy[a] -= sg * (1.0f - tt) * dy;
-                        gsx[c] -= sg * tt * dx;
-                        gsy[c] -= sg * tt * dy;
-                    }
-                }
-            }
+    for (int i = 0; i < 3; i++) {
+        gsx[i] = (float)(-l[i] * Gx);
+        gsy[i] = (float)(-l[i] * Gy);
+    }
+    if (want_dist && gdist != 0.0f) {
+        int ne;
+        dr_distnorm(s.X, s.Y, px, py, E, (float)W * 256.0f, ne);
+        int a = (ne + 1) % 3, c = (ne + 2) % 3;
+        float sxa = (float)s.X[a] * (1.0f / 256.0f), sya = (float)s.Y[a] * (1.0f / 256.0f);
+        float sxc = (float)s.X[c] * (1.0f / 256.0f), syc = (float)s.Y[c] * (1.0f / 256.0f);
+        float Px = (float)x + 0.5f, Py = (float)y + 0.5f;
+        float ex = sxc - sxa, ey = syc - sya;
+        float tt = ((Px - sxa) * ex + (Py - sya) * ey) / (ex * ex + ey * ey);
+        tt = fminf(fmaxf(tt, 0.0f), 1.0f);
+        float cx = sxa + tt * ex, cy = sya + tt * ey;
+        float dx = Px - cx, dy = Py - cy;
+        float d = sqrtf(dx * dx + dy * dy);
+        if (d > 0.0f) {
+            float sg = (in ? gdist : -gdist) / ((float)W * d);
+            gsx[a] -= sg * (1.0f - tt) * dx;
+            gsy[a] -= sg * (1.0f - tt) * dy;
+            gsx[c] -= sg * tt * dx;
+            gsy[c] -= sg * tt * dy;
         }
-    // screen -> clip: x_s = (x/w + 1) W/2, y_s = (1 - y/w) H/2
-    const float hw = 0.5f * (float)W, hh = 0.5f * (float)H;
-    const float4 *pc = pos_clip + (int64_t)b * V;
+    }
 #pragma unroll
     for (int i = 0; i < 3; i++) {
         int corner = dr_corner(s.meta, i);
-        float4 p = pc[vid[corner]];
-        float xn = p.x / p.w, yn = p.y / p.w;
-        double w = p.w;
-        double gx = gsx[i] * hw / w;
-        double gy = -gsy[i] * hh / w;
-        double gww = (-gsx[i] * hw * xn + gsy[i] * hh * yn) / w + gw[i];
-        cg[corner * 3 + 0] = (float)gx;
-        cg[corner * 3 + 1] = (float)gy;
-        cg[corner * 3 + 2] = (float)gww;
+        out[corner * 3 + 0] = gsx[i];
+        out[corner * 3 + 1] = gsy[i];
+        out[corner * 3 + 2] = (float)gw[i];
+    }
+}
+
+__global__ void __launch_bounds__(DRESSI_TILE_PIX)
+    k_rast_bwd_tile(const float4 *__restrict__ pos_clip, const int32_t *__restrict__ tris, int V, int T,
+                    int H, int W, int K, int cull, int margin, const int32_t *__restrict__ tri_id,
+                    FragLists fl, int ntx, int nt, const float2 *__restrict__ grad_bary,
+                    const float *__restrict__ grad_dist, float *__restrict__ partial) {
+    extern __shared__ float vals[];   // [K*256][9]
+    const int bt = blockIdx.x;
+    const int nf = fl.n_frag[bt];
+    if (nf == 0) return;
+    const int b = bt / nt, tile = bt - b * nt;
+    const int tx = tile % ntx, ty = tile / ntx;
+    const int p = threadIdx.x;
+    const int x = tx * DRESSI_TILE + (p & (DRESSI_TILE - 1));
+    const int y = ty * DRESSI_TILE + p / DRESSI_TILE;
+    const float4 *pc = pos_clip + (int64_t)b * V;
+    if (x < W && y < H) {
+        for (int k = 0; k < K; k++) {
+            int64_t o = (((int64_t)b * K + k) * H + y) * W + x;
+            int t = tri_id[o];
+            if (t < 0 || t >= T) continue;
+            const int32_t *tv = tris + 3 * (int64_t)t;
+            TriSetup s = dr_setup(pc, tv[0], tv[1], tv[2], H, W, cull, margin);
+            float *dst = vals + (k * DRESSI_TILE_PIX + p) * 9;
+            if (!(s.meta & 1)) {
+#pragma unroll
+                for (int c = 0; c < 9; c++) dst[c] = 0.0f;
+                continue;
+            }
+            float gd = grad_dist ? grad_dist[o] : 0.0f;
+            float g9[9];
+            rast_frag_grad(s, x, y, grad_bary[o], gd, grad_dist != nullptr, W, g9);
+#pragma unroll
+            for (int c = 0; c < 9; c++) dst[c] = g9[c];
+        }
+    }
+    __syncthreads();
+    const int64_t base = (int64_t)bt * DRESSI_TILE_PIX * K;
+    const int nr = fl.n_rec[bt];
+    for (int r = p; r < nr; r += DRESSI_TILE_PIX) {
+        int j0 = fl.rec_start[base + r];
+        int j1 = (r + 1 < nr) ? fl.rec_start[base + r + 1] : nf;
+        float acc[9];
+#pragma unroll
+        for (int c = 0; c < 9; c++) acc[c] = 0.0f;
+        for (int j = j0; j < j1; j++) {
+            const float *v = vals + (int)fl.frag[base + j] * 9;
+#pragma unroll
+            for (int c = 0; c < 9; c++) acc[c] += v[c];
+        }
+        float *dst = partial + (base + r) * 9;
+#pragma unroll
+        for (int c = 0; c < 9; c++) dst[c] = acc[c];
+    }
+}
+
+// per (view, triangle): sum its tile records, map screen -> clip
+// (x_s = (x/w + 1) W/2, y_s = (1 - y/w) H/2)
+__global__ void k_rast_bwd_sum(const float4 *__restrict__ pos_clip, const int32_t *__restrict__ tris,
+                               int B, int V, int T, int H, int W, int K, TriTiles tt,
+                               const float *__restrict__ partial, float *__restrict__ corner_grad) {
+    int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= (int64_t)B * T) return;
+    int b = (int)(gid / T), t = (int)(gid - (int64_t)b * T);
+    double acc[9];
+#pragma unroll
+    for (int c = 0; c < 9; c++) acc[c] = 0.0;
+    for (int e = tt.offsets[gid]; e < tt.offsets[gid + 1]; e++) {
+        int2 ent = tt.entries[e];
+        const float *v = partial + ((int64_t)ent.x * DRESSI_TILE_PIX * K + ent.y) * 9;
+#pragma unroll
+        for (int c = 0; c < 9; c++) acc[c] += (double)v[c];
+    }
+    float *cg = corner_grad + gid * 9;
+    const int32_t *tv = tris + 3 * (int64_t)t;
+    const double hw = 0.5 * (double)W, hh = 0.5 * (double)H;
+#pragma unroll
+    for (int i = 0; i < 3; i++) {
+        int v = tv[i];
+        if (v < 0 || v >= V) {
+            cg[3 * i] = cg[3 * i + 1] = cg[3 * i + 2] = 0.0f;
+            continue;
+        }
+        float4 p = pos_clip[(int64_t)b * V + v];
+        double w = p.w, xn = (double)(p.x / p.w), yn = (double)(p.y / p.w);
+        double gsx = acc[3 * i], gsy = acc[3 * i + 1];
+        cg[3 * i + 0] = (float)(gsx * hw / w);
+        cg[3 * i + 1] = (float)(-gsy * hh / w);
+        cg[3 * i + 2] = (float)((-gsx * hw * xn + gsy * hh * yn) / w + acc[3 * i + 2]);
     }
 }
 
@@ -667,10 +764,15 @@ __global__ void k_vertex_gather_pos(const float *__restrict__ corner_grad, Adjac
     grad_pos[gid] = make_float4(gx, gy, 0.0f, gw);
 }
 
+static size_t partial_floats(int B, int K, int H, int W, int per) {
+    return (size_t)B * tiles_x(W) * tiles_y(H) * DRESSI_TILE_PIX * K * per;
+}
+
 extern "C" int dressi_rasterize_bwd(dressi_ctx *ctx, const float *pos_clip, const int32_t *tris,
                                     int B, int V, int T, int H, int W, int K, float r, int cull,
                                     const int32_t *tri_id, const float *grad_bary,
-                                    const float *grad_dist, float *grad_pos_clip, void *stream) {
+                                    const float *grad_dist, const void *frag_index,
+                                    const int32_t *adj, float *grad_pos_clip, void *stream) {
     int rc = check_raster_args(ctx, pos_clip, tris, B, V, T, H, W, K, r);
     if (rc) return rc;
     if (!tri_id || !grad_bary || (!grad_pos_clip && B * (int64_t)V > 0))
@@ -680,25 +782,48 @@ extern "C" int dressi_rasterize_bwd(dressi_ctx *ctx, const float *pos_clip, cons
     int ntx = tiles_x(W), nt = ntx * tiles_y(H);
     int margin = soft_margin(r, W);
     Carver c;
-    size_t o_fl = c.take(dressi_fraglists_bytes(B, H, W, K));
-    size_t o_adj = c.take(dressi_adjacency_bytes(V, T));
+    size_t o_fi = frag_index ? 0 : c.take(dressi_fragindex_bytes(B, K, H, W, T));
+    size_t o_adj = adj ? 0 : c.take(adjacency_buf_bytes(V, T));
+    size_t o_tmp = c.take(std::max(frag_index ? (size_t)0 : dressi_fragindex_tmp_bytes(B, T),
+                                   adj ? (size_t)0 : dressi_adjacency_tmp_bytes(V)));
+    size_t o_part = c.take(sizeof(float) * partial_floats(B, K, H, W, 9));
     size_t o_cg = c.take(sizeof(float) * 9 * (size_t)B * T);
     rc = dressi_scratch(ctx, c.off, st);
     if (rc) return rc;
+    if (!frag_index) {
+        rc = dressi_counters(ctx, (size_t)B * T, st);
+        if (rc) return rc;
+    }
     void *S = ctx->scratch;
+    void *fi = const_cast<void *>(frag_index);
+    if (!fi) {
+        fi = at<void>(S, o_fi);
+        dressi_build_fragindex(tri_id, B, K, H, W, T, fi, at<void>(S, o_tmp), ctx->counters, st);
+    }
     FragLists fl;
-    dressi_build_fraglists(tri_id, B, K, H, W, at<void>(S, o_fl), fl, st);
-    Adjacency adj;
-    dressi_build_adjacency(tris, T, V, at<void>(S, o_adj), adj, st);
+    TriTiles tt;
+    dressi_fragindex_view(fi, B, K, H, W, T, fl, tt);
+    const int32_t *ab = adj;
+    if (!ab) {
+        int32_t *buf = at<int32_t>(S, o_adj);
+        dressi_build_adjacency_into(tris, T, V, buf, at<void>(S, o_tmp), st);
+        ab = buf;
+    }
+    Adjacency A = adjacency_view(ab, V);
+    float *part = at<float>(S, o_part);
     float *cg = at<float>(S, o_cg);
     int64_t ntri = (int64_t)B * T;
+    if ((int64_t)B * nt > 0)
+        DR_LAUNCH("k_rast_bwd_tile", (k_rast_bwd_tile), B * nt, DRESSI_TILE_PIX,
+                  sizeof(float) * 9 * DRESSI_TILE_PIX * K, st, reinterpret_cast<const float4 *>(pos_clip), tris,
+                  V, T, H, W, K, cull, margin, tri_id, fl, ntx, nt, reinterpret_cast<const float2 *>(grad_bary),
+                  grad_dist, part);
     if (ntri > 0)
-        DR_LAUNCH("k_rast_bwd_tri", (k_rast_bwd_tri), (int)((ntri + 127) / 128), 128, 0, st, 
-            reinterpret_cast<const float4 *>(pos_clip), tris, B, V, T, H, W, K, cull, margin, ntx,
-            nt, fl, reinterpret_cast<const float2 *>(grad_bary), grad_dist, cg);
+        DR_LAUNCH("k_rast_bwd_sum", (k_rast_bwd_sum), (int)((ntri + 255) / 256), 256, 0, st,
+                  reinterpret_cast<const float4 *>(pos_clip), tris, B, V, T, H, W, K, tt, part, cg);
     int64_t nv = (int64_t)B * V;
-    DR_LAUNCH("k_vertex_gather_pos", (k_vertex_gather_pos), (int)((nv + 255) / 256), 256, 0, st, 
-        cg, adj, B, V, T, reinterpret_cast<float4 *>(grad_pos_clip));
+    DR_LAUNCH("k_vertex_gather_pos", (k_vertex_gather_pos), (int)((nv + 255) / 256), 256, 0, st, cg, A, B,
+              V, T, reinterpret_cast<float4 *>(grad_pos_clip));
     return dressi_launch_check(ctx, "rasterize_bwd");
 }
 
@@ -710,38 +835,34 @@ extern "C" size_t dressi_scratch_bytes(int B, int V, int T, int H, int W, int K,
     if (B < 0 || V < 0 || T < 0 || H < 0 || W < 0 || K < 1) return 0;
     int nt = tiles_x(W) * tiles_y(H);
     int margin = soft_margin(r, W);
+    int Vm = Va > V ? Va : V;
     size_t need = 0;
+    auto upd = [&](size_t v) { need = v > need ? v : need; };
     {
         Carver c;
-        size_t o[6];
-        raster_scratch(B, T, nt, default_bin_capacity(B, T, nt, margin), c, o);
-        need = c.off > need ? c.off : need;
+        size_t o[2];
+        raster_scratch(B, T, nt, default_tile_capacity(B, T, nt, margin), c, o);
+        upd(c.off);
     }
-    {
+    {   // a backward call that builds its own fragment index and adjacency
         Carver c;
-        c.take(dressi_fraglists_bytes(B, H, W, K));
-        c.take(dressi_adjacency_bytes(V, T));
-        c.take(sizeof(float) * 9 * (size_t)B * T);
-        need = c.off > need ? c.off : need;
-    }
-    {
-        Carver c;
-        c.take(dressi_fraglists_bytes(B, H, W, K));
-        c.take(dressi_tritiles_bytes(B, T, H, W, K));
-        c.take(dressi_adjacency_bytes(Va > V ? Va : V, T));
-        c.take(sizeof(float) * 3 * (size_t)(C > 0 ? C : 1) * B * T);
-        need = c.off > need ? c.off : need;
+        c.take(dressi_fragindex_bytes(B, K, H, W, T));
+        c.take(adjacency_buf_bytes(Vm, T));
+        c.take(std::max(dressi_fragindex_tmp_bytes(B, T), dressi_adjacency_tmp_bytes(Vm)));
+        c.take(sizeof(float) * 3 * (size_t)(C > 9 ? C : 9) * B * T);
+        c.take(sizeof(float) * partial_floats(B, K, H, W, 3 * (C > 3 ? C : 3)));
+        upd(c.off);
     }
     {
         Carver c;
         c.take(sizeof(int32_t) * (size_t)tex_cells * (tex_slices > 0 ? tex_slices : 1));
-        need = c.off > need ? c.off : need;
+        upd(c.off);
     }
     {
         Carver c;
         c.take((size_t)B * H * W);
         c.take((size_t)B * H * W);
-        need = c.off > need ? c.off : need;
+        upd(c.off);
     }
     return need;
 }

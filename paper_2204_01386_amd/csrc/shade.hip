@@ -89,33 +89,30 @@ __device__ __forceinline__ float3 normalize3_bwd(float3 a, float3 g) {
     return (1.0f / l) * (g - dot3(g, n) * n);
 }
 
-__global__ void k_face_normals(const float *__restrict__ pos, const int32_t *__restrict__ tris, int T,
-                               int V, float *__restrict__ fn) {
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= T) return;
+__device__ __forceinline__ float3 face_normal(const float *pos, const int32_t *tris, int t, int V,
+                                              int *vid) {
     int a = tris[3 * t], b = tris[3 * t + 1], c = tris[3 * t + 2];
-    float3 n = make_float3(0.0f, 0.0f, 0.0f);
-    if (a >= 0 && a < V && b >= 0 && b < V && c >= 0 && c < V) {
-        float3 p0 = ld3(pos + 3 * (int64_t)a);
-        n = cross3(ld3(pos + 3 * (int64_t)b) - p0, ld3(pos + 3 * (int64_t)c) - p0);
-    }
-    fn[3 * (int64_t)t] = n.x;
-    fn[3 * (int64_t)t + 1] = n.y;
-    fn[3 * (int64_t)t + 2] = n.z;
+    vid[0] = a; vid[1] = b; vid[2] = c;
+    if (a < 0 || a >= V || b < 0 || b >= V || c < 0 || c >= V) return make_float3(0.0f, 0.0f, 0.0f);
+    float3 p0 = ld3(pos + 3 * (int64_t)a);
+    return cross3(ld3(pos + 3 * (int64_t)b) - p0, ld3(pos + 3 * (int64_t)c) - p0);
 }
 
-__device__ __forceinline__ float3 vertex_acc(const float *fn, const Adjacency &adj, int v) {
+// sum of the (area-weighted) normals of the faces around v, corners ascending
+__device__ __forceinline__ float3 vertex_acc(const float *pos, const int32_t *tris, const Adjacency &adj,
+                                            int v, int V) {
     float3 s = make_float3(0.0f, 0.0f, 0.0f);
-    for (int j = adj.offsets[v]; j < adj.offsets[v + 1]; j++) s = s + ld3(fn + 3 * (int64_t)(adj.corners[j] / 3));
+    int vid[3];
+    for (int j = adj.offsets[v]; j < adj.offsets[v + 1]; j++) s = s + face_normal(pos, tris, adj.corners[j] / 3, V, vid);
     return s;
 }
 
-__global__ void k_vertex_attrs(const float *__restrict__ pos, const float *__restrict__ extra,
-                               const float *__restrict__ fn, Adjacency adj, int V, int C,
+__global__ void k_vertex_attrs(const float *__restrict__ pos, const int32_t *__restrict__ tris,
+                               const float *__restrict__ extra, Adjacency adj, int V, int C,
                                float *__restrict__ out) {
     int v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= V) return;
-    float3 n = normalize3(vertex_acc(fn, adj, v));
+    float3 n = normalize3(vertex_acc(pos, tris, adj, v, V));
     float *o = out + (int64_t)v * C;
     o[0] = n.x; o[1] = n.y; o[2] = n.z;
     o[3] = pos[3 * (int64_t)v]; o[4] = pos[3 * (int64_t)v + 1]; o[5] = pos[3 * (int64_t)v + 2];
@@ -124,75 +121,74 @@ __global__ void k_vertex_attrs(const float *__restrict__ pos, const float *__res
     }
 }
 
-__global__ void k_vertex_attrs_bwd1(const float *__restrict__ fn, Adjacency adj, int V, int C,
-                                    const float *__restrict__ g, float *__restrict__ gacc) {
+// gradient w.r.t. the un-normalised vertex normal sum
+__global__ void k_vertex_attrs_bwd1(const float *__restrict__ pos, const int32_t *__restrict__ tris,
+                                    Adjacency adj, int V, int C, const float *__restrict__ g,
+                                    float *__restrict__ gacc) {
     int v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= V) return;
-    float3 a = vertex_acc(fn, adj, v);
+    float3 a = vertex_acc(pos, tris, adj, v, V);
     float3 r = normalize3_bwd(a, ld3(g + (int64_t)v * C));
     gacc[3 * (int64_t)v] = r.x;
     gacc[3 * (int64_t)v + 1] = r.y;
     gacc[3 * (int64_t)v + 2] = r.z;
 }
 
-// per face: n = e1 x e2 -> corner gradients (c0: -(g1+g2), c1: g1, c2: g2)
+// per vertex: position column + grad_pos_in + the corner gradients of the
+// cross products of its faces (n = e1 x e2: ge1 = e2 x gn, ge2 = gn x e1;
+// corner 0 gets -(ge1 + ge2), corner 1 ge1, corner 2 ge2), corners ascending
 __global__ void k_vertex_attrs_bwd2(const float *__restrict__ pos, const int32_t *__restrict__ tris,
-                                    int T, int V, const float *__restrict__ gacc,
-                                    float *__restrict__ cg) {
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= T) return;
-    int a = tris[3 * t], b = tris[3 * t + 1], c = tris[3 * t + 2];
-    float3 g1 = make_float3(0.0f, 0.0f, 0.0f), g2 = g1;
-    if (a >= 0 && a < V && b >= 0 && b < V && c >= 0 && c < V) {
-        float3 gn = ld3(gacc + 3 * (int64_t)a) + ld3(gacc + 3 * (int64_t)b) + ld3(gacc + 3 * (int64_t)c);
-        float3 p0 = ld3(pos + 3 * (int64_t)a);
-        float3 e1 = ld3(pos + 3 * (int64_t)b) - p0, e2 = ld3(pos + 3 * (int64_t)c) - p0;
-        g1 = cross3(e2, gn);
-        g2 = cross3(gn, e1);
-    }
-    float3 g0 = make_float3(-(g1.x + g2.x), -(g1.y + g2.y), -(g1.z + g2.z));
-    float *o = cg + 9 * (int64_t)t;
-    o[0] = g0.x; o[1] = g0.y; o[2] = g0.z;
-    o[3] = g1.x; o[4] = g1.y; o[5] = g1.z;
-    o[6] = g2.x; o[7] = g2.y; o[8] = g2.z;
-}
-
-__global__ void k_vertex_attrs_bwd3(const float *__restrict__ cg, Adjacency adj, int V, int C,
-                                    const float *__restrict__ g, const float *__restrict__ gin,
+                                    Adjacency adj, int V, int C, const float *__restrict__ g,
+                                    const float *__restrict__ gin, const float *__restrict__ gacc,
                                     float *__restrict__ grad_pos) {
     int v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= V) return;
     float3 s = ld3(g + (int64_t)v * C + 3);
     if (gin) s = s + ld3(gin + 3 * (int64_t)v);
-    for (int j = adj.offsets[v]; j < adj.offsets[v + 1]; j++) s = s + ld3(cg + 3 * (int64_t)adj.corners[j]);
+    for (int j = adj.offsets[v]; j < adj.offsets[v + 1]; j++) {
+        int cr = adj.corners[j];
+        int t = cr / 3, i = cr - 3 * t;
+        int a = tris[3 * t], b = tris[3 * t + 1], c = tris[3 * t + 2];
+        if (a < 0 || a >= V || b < 0 || b >= V || c < 0 || c >= V) continue;
+        float3 gn = ld3(gacc + 3 * (int64_t)a) + ld3(gacc + 3 * (int64_t)b) + ld3(gacc + 3 * (int64_t)c);
+        float3 p0 = ld3(pos + 3 * (int64_t)a);
+        float3 e1 = ld3(pos + 3 * (int64_t)b) - p0, e2 = ld3(pos + 3 * (int64_t)c) - p0;
+        float3 g1 = cross3(e2, gn), g2 = cross3(gn, e1);
+        if (i == 0) s = s - (g1 + g2);
+        else if (i == 1) s = s + g1;
+        else s = s + g2;
+    }
     grad_pos[3 * (int64_t)v] = s.x;
     grad_pos[3 * (int64_t)v + 1] = s.y;
     grad_pos[3 * (int64_t)v + 2] = s.z;
 }
 
 extern "C" int dressi_vertex_attrs(dressi_ctx *ctx, const float *pos, const int32_t *tris, int V, int T,
-                                   const float *extra, float *out, void *stream) {
+                                   const float *extra, const int32_t *adj, float *out, void *stream) {
     if (!ctx) return DRESSI_EINVAL;
     if (V < 0 || T < 0) return dressi_fail(ctx, DRESSI_EINVAL, "vertex_attrs: bad dimensions");
     if (V == 0) return DRESSI_OK;
     if (!pos || !out || (T > 0 && !tris)) return dressi_fail(ctx, DRESSI_EINVAL, "vertex_attrs: null pointer");
     hipStream_t st = (hipStream_t)stream;
-    Carver c;
-    size_t o_adj = c.take(dressi_adjacency_bytes(V, T));
-    size_t o_fn = c.take(sizeof(float) * 3 * (size_t)(T > 0 ? T : 1));
-    int rc = dressi_scratch(ctx, c.off, st);
-    if (rc) return rc;
-    Adjacency adj;
-    dressi_build_adjacency(tris, T, V, at<void>(ctx->scratch, o_adj), adj, st);
-    float *fn = at<float>(ctx->scratch, o_fn);
-    if (T > 0) DR_LAUNCH("k_face_normals", (k_face_normals), (T + 255) / 256, 256, 0, st, pos, tris, T, V, fn);
+    const int32_t *ab = adj;
+    if (!ab) {
+        Carver c;
+        size_t o_adj = c.take(adjacency_buf_bytes(V, T));
+        size_t o_tmp = c.take(dressi_adjacency_tmp_bytes(V));
+        int rc = dressi_scratch(ctx, c.off, st);
+        if (rc) return rc;
+        int32_t *buf = at<int32_t>(ctx->scratch, o_adj);
+        dressi_build_adjacency_into(tris, T, V, buf, at<void>(ctx->scratch, o_tmp), st);
+        ab = buf;
+    }
+    Adjacency A = adjacency_view(ab, V);
     int C = extra ? 9 : 6;
-    DR_LAUNCH("k_vertex_attrs", (k_vertex_attrs), (V + 255) / 256, 256, 0, st, pos, extra, fn, adj, V, C, out);
+    DR_LAUNCH("k_vertex_attrs", (k_vertex_attrs), (V + 255) / 256, 256, 0, st, pos, tris, extra, A, V, C, out);
     return dressi_launch_check(ctx, "vertex_attrs");
 }
 
 extern "C" int dressi_vertex_attrs_bwd(dressi_ctx *ctx, const float *pos, const int32_t *tris, int V,
-                                       int T, int C, const float *grad_out,
+                                       int T, int C, const int32_t *adj, const float *grad_out,
                                        const float *grad_pos_in, float *grad_pos, void *stream) {
     if (!ctx) return DRESSI_EINVAL;
     if (V < 0 || T < 0 || (C != 6 && C != 9))
@@ -202,21 +198,24 @@ extern "C" int dressi_vertex_attrs_bwd(dressi_ctx *ctx, const float *pos, const 
         return dressi_fail(ctx, DRESSI_EINVAL, "vertex_attrs_bwd: null pointer");
     hipStream_t st = (hipStream_t)stream;
     Carver c;
-    size_t o_adj = c.take(dressi_adjacency_bytes(V, T));
-    size_t o_fn = c.take(sizeof(float) * 3 * (size_t)(T > 0 ? T : 1));
+    size_t o_adj = adj ? 0 : c.take(adjacency_buf_bytes(V, T));
+    size_t o_tmp = adj ? 0 : c.take(dressi_adjacency_tmp_bytes(V));
     size_t o_ga = c.take(sizeof(float) * 3 * (size_t)V);
-    size_t o_cg = c.take(sizeof(float) * 9 * (size_t)(T > 0 ? T : 1));
     int rc = dressi_scratch(ctx, c.off, st);
     if (rc) return rc;
     void *S = ctx->scratch;
-    Adjacency adj;
-    dressi_build_adjacency(tris, T, V, at<void>(S, o_adj), adj, st);
-    float *fn = at<float>(S, o_fn), *ga = at<float>(S, o_ga), *cg = at<float>(S, o_cg);
-    if (T > 0) DR_LAUNCH("k_face_normals", (k_face_normals), (T + 255) / 256, 256, 0, st, pos, tris, T, V, fn);
-    DR_LAUNCH("k_vertex_attrs_bwd1", (k_vertex_attrs_bwd1), (V + 255) / 256, 256, 0, st, fn, adj, V, C, grad_out, ga);
-    if (T > 0) DR_LAUNCH("k_vertex_attrs_bwd2", (k_vertex_attrs_bwd2), (T + 255) / 256, 256, 0, st, pos, tris, T, V, ga, cg);
-    DR_LAUNCH("k_vertex_attrs_bwd3", (k_vertex_attrs_bwd3), (V + 255) / 256, 256, 0, st, cg, adj, V, C, grad_out, grad_pos_in,
-                                                         grad_pos);
+    const int32_t *ab = adj;
+    if (!ab) {
+        int32_t *buf = at<int32_t>(S, o_adj);
+        dressi_build_adjacency_into(tris, T, V, buf, at<void>(S, o_tmp), st);
+        ab = buf;
+    }
+    Adjacency A = adjacency_view(ab, V);
+    float *ga = at<float>(S, o_ga);
+    DR_LAUNCH("k_vertex_attrs_bwd1", (k_vertex_attrs_bwd1), (V + 255) / 256, 256, 0, st, pos, tris, A, V, C,
+              grad_out, ga);
+    DR_LAUNCH("k_vertex_attrs_bwd2", (k_vertex_attrs_bwd2), (V + 255) / 256, 256, 0, st, pos, tris, A, V, C,
+              grad_out, grad_pos_in, ga, grad_pos);
     return dressi_launch_check(ctx, "vertex_attrs_bwd");
 }
 
@@ -436,13 +435,15 @@ extern "C" int dressi_shade_bwd(dressi_ctx *ctx, int mode, const dressi_frag_in 
 // L2 loss with a fixed-order reduction
 // ---------------------------------------------------------------------------
 #define LOSS_BS 256
-#define LOSS_MAX_BLOCKS 1024
+#define LOSS_MAX_BLOCKS 128   // few blocks: one completion atomic each
 
 __global__ void __launch_bounds__(LOSS_BS)
     k_loss_l2(const float *__restrict__ color, const float *__restrict__ sil,
               const float *__restrict__ target, int64_t n, float inv, float *__restrict__ grad_color,
-              float *__restrict__ grad_sil, float *__restrict__ partial) {
+              float *__restrict__ grad_sil, float *__restrict__ partial, int32_t *__restrict__ done,
+              float *__restrict__ loss) {
     __shared__ float red[LOSS_BS];
+    __shared__ int last;
     float acc = 0.0f;
     for (int64_t i = (int64_t)blockIdx.x * LOSS_BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * LOSS_BS) {
         float4 t = reinterpret_cast<const float4 *>(target)[i];
@@ -462,21 +463,27 @@ __global__ void __launch_bounds__(LOSS_BS)
         if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
         __syncthreads();
     }
-    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
-}
-
-__global__ void __launch_bounds__(LOSS_BS) k_loss_final(const float *__restrict__ partial, int nb, float inv,
-                                                        float *__restrict__ loss) {
-    __shared__ float red[LOSS_BS];
-    float acc = 0.0f;
-    for (int i = threadIdx.x; i < nb; i += LOSS_BS) acc += partial[i];
-    red[threadIdx.x] = acc;
+    if (threadIdx.x == 0) {
+        partial[blockIdx.x] = red[0];
+        __threadfence();
+        last = atomicAdd(done, 1) == (int)gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!last) return;
+    // the last block to finish sums the per-block partials in a fixed order
+    __threadfence();
+    float a2 = 0.0f;
+    for (int i = threadIdx.x; i < (int)gridDim.x; i += LOSS_BS) a2 += __builtin_nontemporal_load(&partial[i]);
+    red[threadIdx.x] = a2;
     __syncthreads();
     for (int s = LOSS_BS / 2; s > 0; s >>= 1) {
         if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
         __syncthreads();
     }
-    if (threadIdx.x == 0) loss[0] = red[0] * inv;
+    if (threadIdx.x == 0) {
+        loss[0] = red[0] * inv;
+        *done = 0;   // leave the counter at zero
+    }
 }
 
 extern "C" int dressi_loss_l2(dressi_ctx *ctx, const float *color, const float *sil, const float *target,
@@ -495,9 +502,11 @@ extern "C" int dressi_loss_l2(dressi_ctx *ctx, const float *color, const float *
     size_t o_p = c.take(sizeof(float) * nb);
     int rc = dressi_scratch(ctx, c.off, st);
     if (rc) return rc;
+    rc = dressi_counters(ctx, 1, st);
+    if (rc) return rc;
     float *partial = at<float>(ctx->scratch, o_p);
-    float inv = n > 0 ? 1.0f / (4.0f * (float)n) : 0.0f;
-    DR_LAUNCH("k_loss_l2", (k_loss_l2), nb, LOSS_BS, 0, st, color, sil, target, n, inv, grad_color, grad_sil, partial);
-    DR_LAUNCH("k_loss_final", (k_loss_final), 1, LOSS_BS, 0, st, partial, nb, 1.0f / (4.0f * (float)(n > 0 ? n : 1)), loss);
+    float inv = 1.0f / (4.0f * (float)(n > 0 ? n : 1));
+    DR_LAUNCH("k_loss_l2", (k_loss_l2), nb, LOSS_BS, 0, st, color, sil, target, n, inv, grad_color, grad_sil,
+              partial, ctx->counters, loss);
     return dressi_launch_check(ctx, "loss_l2");
 }

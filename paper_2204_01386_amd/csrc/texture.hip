@@ -131,20 +131,40 @@ __global__ void k_tex_fwd(const float *__restrict__ tex, dressi_tex_desc td,
     for (int c = 0; c < Ct; c++) y[c] = w00 * p00[c] + w01 * p01[c] + w10 * p10[c] + w11 * p11[c];
 }
 
-// d out / d coord
-__global__ void k_tex_bwd_coord(const float *__restrict__ tex, dressi_tex_desc td,
+// Per pixel: d out / d coord and, when `inv` is given, the inverse-UV record
+// (the pixel index written into its cell with atomicMax).
+__global__ void k_tex_bwd_pixel(const float *__restrict__ tex, dressi_tex_desc td,
                                 const float *__restrict__ coord, const int32_t *__restrict__ tri_id,
-                                int64_t n, const float *__restrict__ grad_out,
-                                float *__restrict__ grad_coord) {
+                                int64_t npix, int S, const float *__restrict__ grad_out,
+                                float *__restrict__ grad_coord, int32_t *__restrict__ inv) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    if (i >= (int64_t)S * npix) return;
     const int Ct = td.Ct;
-    const int cd = td.kind == DRESSI_TEX_CUBE ? 3 : 2;
-    float *gc = grad_coord + i * cd;
+    const bool cube = td.kind == DRESSI_TEX_CUBE;
+    const int cd = cube ? 3 : 2;
     const float *q = coord + i * cd;
     Taps t;
     t.ok = 0;
-    if (!tri_id || tri_id[i] >= 0) t = make_taps(td, q);
+    bool covered = !tri_id || tri_id[i] >= 0;
+    if (covered) t = make_taps(td, q);
+    if (inv && covered && t.ok) {
+        int s = (int)(i / npix);
+        int pix = (int)(i - (int64_t)s * npix);
+        int cx, cy;
+        if (cube) {
+            float u, v, sc, tc, ma;
+            cube_face(q[0], q[1], q[2], u, v, sc, tc, ma);
+            cx = cell1d(u, td.Wt, DRESSI_WRAP_CLAMP);
+            cy = cell1d(v, td.Ht, DRESSI_WRAP_CLAMP);
+        } else {
+            cx = cell1d(q[0], td.Wt, td.wrap_u);
+            cy = cell1d(q[1], td.Ht, td.wrap_v);
+        }
+        int64_t cells = (int64_t)(cube ? 6 : 1) * td.Ht * td.Wt;
+        atomicMax(&inv[(int64_t)s * cells + ((int64_t)t.face * td.Ht + cy) * td.Wt + cx], pix);
+    }
+    if (!grad_coord) return;
+    float *gc = grad_coord + i * cd;
     if (!t.ok) {
         for (int j = 0; j < cd; j++) gc[j] = 0.0f;
         return;
@@ -162,7 +182,7 @@ __global__ void k_tex_bwd_coord(const float *__restrict__ tex, dressi_tex_desc t
     }
     du *= (float)td.Wt;
     dv *= (float)td.Ht;
-    if (td.kind != DRESSI_TEX_CUBE) {
+    if (!cube) {
         gc[0] = du;
         gc[1] = dv;
         return;
@@ -187,92 +207,81 @@ __global__ void k_tex_bwd_coord(const float *__restrict__ tex, dressi_tex_desc t
     gc[2] = g3[2];
 }
 
-// inverse UV: each covered pixel writes max(pixel index) into its cell
-__global__ void k_invuv_build(dressi_tex_desc td, const float *__restrict__ coord,
-                              const int32_t *__restrict__ tri_id, int64_t npix, int S,
-                              int32_t *__restrict__ inv) {
-    int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid >= (int64_t)S * npix) return;
-    if (tri_id[gid] < 0) return;
-    int s = (int)(gid / npix);
-    int i = (int)(gid - (int64_t)s * npix);
-    const int cd = td.kind == DRESSI_TEX_CUBE ? 3 : 2;
-    const float *q = coord + gid * cd;
-    int f = 0, cx, cy;
-    if (td.kind == DRESSI_TEX_CUBE) {
-        float u, v, sc, tc, ma;
-        f = cube_face(q[0], q[1], q[2], u, v, sc, tc, ma);
-        if (f < 0) return;
-        cx = cell1d(u, td.Wt, DRESSI_WRAP_CLAMP);
-        cy = cell1d(v, td.Ht, DRESSI_WRAP_CLAMP);
-    } else {
-        cx = cell1d(q[0], td.Wt, td.wrap_u);
-        cy = cell1d(q[1], td.Ht, td.wrap_v);
-    }
-    int64_t cells = (int64_t)(td.kind == DRESSI_TEX_CUBE ? 6 : 1) * td.Ht * td.Wt;
-    atomicMax(&inv[(int64_t)s * cells + ((int64_t)f * td.Ht + cy) * td.Wt + cx], i);
-}
-
+// Texture gradient through the inverse UV.  One 16x16 block of texels per
+// workgroup: per slice the 18x18 cells around the block are staged in LDS
+// (wrapped, or -1 outside a clamped texture); blocks whose cells are all
+// empty skip the slice.  Each texel then visits its 3x3 cells in row-major
+// order and adds the kept pixel's gradient times that pixel's bilinear
+// weight on the texel.
+#define IV_T 16
+#define IV_H (IV_T + 2)
 template <int CT>
-__global__ void k_invuv_gather(dressi_tex_desc td, const float *__restrict__ coord, int64_t npix,
-                               int S, const int32_t *__restrict__ inv,
-                               const float *__restrict__ grad_out, float *__restrict__ grad_tex) {
-    const int F = td.kind == DRESSI_TEX_CUBE ? 6 : 1;
+__global__ void __launch_bounds__(IV_T * IV_T)
+    k_invuv_gather(dressi_tex_desc td, const float *__restrict__ coord, int64_t npix, int S,
+                   const int32_t *__restrict__ inv, const float *__restrict__ grad_out,
+                   float *__restrict__ grad_tex) {
+    __shared__ int cells[IV_H * IV_H];
     const int Ht = td.Ht, Wt = td.Wt, Ct = CT > 0 ? CT : td.Ct;
-    const int64_t cells = (int64_t)F * Ht * Wt;
-    int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid >= cells) return;
-    int f = (int)(gid / ((int64_t)Ht * Wt));
-    int rem = (int)(gid - (int64_t)f * Ht * Wt);
-    int ty = rem / Wt, tx = rem - ty * Wt;
-    const int wu = td.kind == DRESSI_TEX_CUBE ? DRESSI_WRAP_CLAMP : td.wrap_u;
-    const int wv = td.kind == DRESSI_TEX_CUBE ? DRESSI_WRAP_CLAMP : td.wrap_v;
-    const int cd = td.kind == DRESSI_TEX_CUBE ? 3 : 2;
+    const bool cube = td.kind == DRESSI_TEX_CUBE;
+    const int F = cube ? 6 : 1;
+    const int wu = cube ? DRESSI_WRAP_CLAMP : td.wrap_u;
+    const int wv = cube ? DRESSI_WRAP_CLAMP : td.wrap_v;
+    const int cd = cube ? 3 : 2;
+    const int f = blockIdx.z;
+    const int bx0 = blockIdx.x * IV_T, by0 = blockIdx.y * IV_T;
+    const int lx = threadIdx.x % IV_T, ly = threadIdx.x / IV_T;
+    const int tx = bx0 + lx, ty = by0 + ly;
+    const bool mine = tx < Wt && ty < Ht;
+    const int64_t cells_all = (int64_t)F * Ht * Wt;
     float acc[16];
 #pragma unroll
     for (int c = 0; c < 16; c++) acc[c] = 0.0f;
-    int cyv[3], cxv[3];
-    bool yok[3], xok[3];
-#pragma unroll
-    for (int d = 0; d < 3; d++) {
-        int cy = ty + d - 1, cx = tx + d - 1;
-        yok[d] = true;
-        xok[d] = true;
-        if (wv == DRESSI_WRAP_REPEAT) cy = (cy % Ht + Ht) % Ht;
-        else yok[d] = cy >= 0 && cy < Ht;
-        if (wu == DRESSI_WRAP_REPEAT) cx = (cx % Wt + Wt) % Wt;
-        else xok[d] = cx >= 0 && cx < Wt;
-        cyv[d] = cy;
-        cxv[d] = cx;
-    }
     for (int s = 0; s < S; s++) {
-        const int32_t *iv = inv + (int64_t)s * cells + (int64_t)f * Ht * Wt;
+        const int32_t *iv = inv + (int64_t)s * cells_all + (int64_t)f * Ht * Wt;
+        int found = 0;
+        for (int h = threadIdx.x; h < IV_H * IV_H; h += IV_T * IV_T) {
+            int cy = by0 - 1 + h / IV_H, cx = bx0 - 1 + h % IV_H;
+            bool ok = true;
+            if (wv == DRESSI_WRAP_REPEAT) cy = ((cy % Ht) + Ht) % Ht;
+            else ok = cy >= 0 && cy < Ht;
+            if (wu == DRESSI_WRAP_REPEAT) cx = ((cx % Wt) + Wt) % Wt;
+            else ok = ok && cx >= 0 && cx < Wt;
+            int v = ok ? iv[(int64_t)cy * Wt + cx] : -1;
+            cells[h] = v;
+            found |= v >= 0;
+        }
+        if (!__syncthreads_or(found)) continue;
+        if (mine) {
 #pragma unroll
-        for (int dy = 0; dy < 3; dy++) {
-            if (!yok[dy]) continue;
+            for (int dy = 0; dy < 3; dy++) {
 #pragma unroll
-            for (int dx = 0; dx < 3; dx++) {
-                if (!xok[dx]) continue;
-                int i = iv[(int64_t)cyv[dy] * Wt + cxv[dx]];
-                if (i < 0) continue;
-                int64_t o = (int64_t)s * npix + i;
-                Taps t = make_taps(td, coord + o * cd);
-                if (!t.ok || t.face != f) continue;
-                float wx0 = 1.0f - t.fx, wx1 = t.fx, wy0 = 1.0f - t.fy, wy1 = t.fy;
-                float w = 0.0f;
-                if (t.y0 == ty && t.x0 == tx) w += wy0 * wx0;
-                if (t.y0 == ty && t.x1 == tx) w += wy0 * wx1;
-                if (t.y1 == ty && t.x0 == tx) w += wy1 * wx0;
-                if (t.y1 == ty && t.x1 == tx) w += wy1 * wx1;
-                if (w == 0.0f) continue;
-                const float *g = grad_out + o * Ct;
+                for (int dx = 0; dx < 3; dx++) {
+                    int i = cells[(ly + dy) * IV_H + lx + dx];
+                    if (i < 0) continue;
+                    int64_t o = (int64_t)s * npix + i;
+                    Taps t = make_taps(td, coord + o * cd);
+                    if (!t.ok || t.face != f) continue;
+                    float w = 0.0f;
+                    if (t.y0 == ty && t.x0 == tx) w += (1.0f - t.fy) * (1.0f - t.fx);
+                    if (t.y0 == ty && t.x1 == tx) w += (1.0f - t.fy) * t.fx;
+                    if (t.y1 == ty && t.x0 == tx) w += t.fy * (1.0f - t.fx);
+                    if (t.y1 == ty && t.x1 == tx) w += t.fy * t.fx;
+                    if (w == 0.0f) continue;
+                    const float *g = grad_out + o * Ct;
 #pragma unroll
-                for (int c = 0; c < 16; c++)
-                    if (c < Ct) acc[c] += w * g[c];
+                    for (int c = 0; c < 16; c++)
+                        if (c < Ct) acc[c] += w * g[c];
+                }
             }
         }
+        __syncthreads();
     }
-    float *gt = grad_tex + gid * Ct;
+    if (!mine) return;
+    float *gt = grad_tex + ((int64_t)f * Ht * Wt + (int64_t)ty * Wt + tx) * Ct;
+    if (Ct == 4) {
+        *reinterpret_cast<float4 *>(gt) = make_float4(acc[0], acc[1], acc[2], acc[3]);
+        return;
+    }
 #pragma unroll
     for (int c = 0; c < 16; c++)
         if (c < Ct) gt[c] = acc[c];
@@ -327,27 +336,34 @@ extern "C" int dressi_texture_bwd(dressi_ctx *ctx, const float *tex, const dress
         ((td->wrap_u == DRESSI_WRAP_REPEAT && td->Wt < 3) || (td->wrap_v == DRESSI_WRAP_REPEAT && td->Ht < 3)))
         return dressi_fail(ctx, DRESSI_EINVAL, "texture_bwd: repeat wrap needs at least 3 texels");
     hipStream_t st = (hipStream_t)stream;
-    if (grad_coord && n > 0)
-        DR_LAUNCH("k_tex_bwd_coord", (k_tex_bwd_coord), (int)((n + 255) / 256), 256, 0, st, tex, *td, coord, tri_id, n, grad_out,
-                                                                grad_coord);
+    int32_t *inv = nullptr;
+    int64_t cells = (int64_t)(td->kind == DRESSI_TEX_CUBE ? 6 : 1) * td->Ht * td->Wt;
     if (grad_tex) {
-        int64_t cells = (int64_t)(td->kind == DRESSI_TEX_CUBE ? 6 : 1) * td->Ht * td->Wt;
         Carver c;
         size_t o_inv = c.take(sizeof(int32_t) * (size_t)cells * (S > 0 ? S : 1));
         rc = dressi_scratch(ctx, c.off, st);
         if (rc) return rc;
-        int32_t *inv = at<int32_t>(ctx->scratch, o_inv);
-        if (n > 0) {
-            dressi_fill_i32(inv, -1, cells * S, st);
-            DR_LAUNCH("k_invuv_build", (k_invuv_build), (int)((n + 255) / 256), 256, 0, st, *td, coord, tri_id, npix, S, inv);
-        }
-        int g = (int)((cells + 255) / 256);
+        inv = at<int32_t>(ctx->scratch, o_inv);
+        if (n > 0) dressi_fill_i32(inv, -1, cells * S, st);
+    }
+    if (n > 0 && (grad_coord || inv))
+        DR_LAUNCH("k_tex_bwd_pixel", (k_tex_bwd_pixel), (int)((n + 255) / 256), 256, 0, st, tex, *td, coord,
+                  tri_id, npix, S, grad_out, grad_coord, inv);
+    if (grad_tex) {
+        dim3 g((unsigned)((td->Wt + IV_T - 1) / IV_T), (unsigned)((td->Ht + IV_T - 1) / IV_T),
+               (unsigned)(td->kind == DRESSI_TEX_CUBE ? 6 : 1));
         if (td->Ct == 4)
-            DR_LAUNCH("k_invuv_gather", (k_invuv_gather<4>), g, 256, 0, st, *td, coord, npix, S, inv, grad_out, grad_tex);
+            DR_LAUNCH("k_invuv_gather", (k_invuv_gather<4>), g, IV_T * IV_T, 0, st, *td, coord, npix, S, inv,
+                      grad_out, grad_tex);
         else if (td->Ct == 3)
-            DR_LAUNCH("k_invuv_gather", (k_invuv_gather<3>), g, 256, 0, st, *td, coord, npix, S, inv, grad_out, grad_tex);
+            DR_LAUNCH("k_invuv_gather", (k_invuv_gather<3>), g, IV_T * IV_T, 0, st, *td, coord, npix, S, inv,
+                      grad_out, grad_tex);
+        else if (td->Ct == 7)
+            DR_LAUNCH("k_invuv_gather", (k_invuv_gather<7>), g, IV_T * IV_T, 0, st, *td, coord, npix, S, inv,
+                      grad_out, grad_tex);
         else
-            DR_LAUNCH("k_invuv_gather", (k_invuv_gather<0>), g, 256, 0, st, *td, coord, npix, S, inv, grad_out, grad_tex);
+            DR_LAUNCH("k_invuv_gather", (k_invuv_gather<0>), g, IV_T * IV_T, 0, st, *td, coord, npix, S, inv,
+                      grad_out, grad_tex);
     }
     return dressi_launch_check(ctx, "texture_bwd");
 }

@@ -132,6 +132,11 @@ class Step:
         self.g_pos_t = e(self.V, 3)
         self.g_pos = e(self.V, 3)
         self.ctx = Bd.context(dev.index)
+        # topology-only structures: built once per mesh
+        self.adj = Bd.dressi_adjacency(self.tris, self.V)
+        self.uv_adj = Bd.dressi_adjacency(self.uv_tris, self.uv.shape[0]) if self.uv is not None else None
+        nbytes = int(_lib.dressi_fragment_index_bytes(B, K, H, W, self.T))
+        self.frag_index = torch.empty(nbytes, dtype=torch.uint8, device=dev)
         self._fin = self._frag_in()
         self._fin_dir = self._frag_in(with_env=False)
 
@@ -163,7 +168,7 @@ class Step:
         h, s = self.ctx.handle, self._s()
         B, V, T, H, W, K = self.B, self.V, self.T, self.H, self.W, self.K
         ck = self._chk
-        ck(_lib.dressi_vertex_attrs(h, _p(self.pos), _p(self.tris), V, T, _p(self.extra),
+        ck(_lib.dressi_vertex_attrs(h, _p(self.pos), _p(self.tris), V, T, _p(self.extra), _p(self.adj),
                                     _p(self.vattr), s), "vertex_attrs")
         ck(_lib.dressi_transform(h, _p(self.pos), _p(self.mvp), B, V, _p(self.pos_clip), s), "transform")
         ck(_lib.dressi_rasterize(h, _p(self.pos_clip), _p(self.tris), B, V, T, H, W, K, self.r, 0,
@@ -198,6 +203,8 @@ class Step:
         B, V, T, H, W, K = self.B, self.V, self.T, self.H, self.W, self.K
         ck = self._chk
         Cv = self.Cv
+        ck(_lib.dressi_fragment_index(h, _p(self.tri_id), B, K, H, W, T, _p(self.frag_index), s),
+           "fragment_index")
         ck(_lib.dressi_softras_bwd(h, _p(self.layer_color), _p(self.dist), _p(self.tri_id), B, K, H, W, 3,
                                    self.sigma, _p(self.E), _p(self.g_color), _p(self.g_sil),
                                    _p(self.g_layer), _p(self.g_dist), s), "softras_bwd")
@@ -229,18 +236,22 @@ class Step:
                                        _p(self.g_uvbuf), s), "texture_bwd")
             ck(_lib.dressi_interpolate_bwd(h, _p(self.uv), 1, self.uv.shape[0], 2, _p(self.uv_tris), T,
                                            _p(self.tri_id), _p(self.bary), B, K, H, W, _p(self.g_uvbuf),
-                                           None, None, _p(self.g_bary_uv), s), "interpolate_bwd uv")
+                                           None, _p(self.frag_index), _p(self.uv_adj), None,
+                                           _p(self.g_bary_uv), s), "interpolate_bwd uv")
             gb_in = self.g_bary_uv
         ck(_lib.dressi_interpolate_bwd(h, _p(self.vattr), 1, V, Cv, _p(self.tris), T, _p(self.tri_id),
                                        _p(self.bary), B, K, H, W, _p(self.g_gbuf), _p(gb_in),
-                                       _p(self.g_vattr), _p(self.g_bary), s), "interpolate_bwd")
+                                       _p(self.frag_index), _p(self.adj), _p(self.g_vattr),
+                                       _p(self.g_bary), s), "interpolate_bwd")
         ck(_lib.dressi_rasterize_bwd(h, _p(self.pos_clip), _p(self.tris), B, V, T, H, W, K, self.r, 0,
-                                     _p(self.tri_id), _p(self.g_bary), _p(self.g_dist), _p(self.g_clip),
-                                     s), "rasterize_bwd")
+                                     _p(self.tri_id), _p(self.g_bary), _p(self.g_dist),
+                                     _p(self.frag_index), _p(self.adj), _p(self.g_clip), s),
+           "rasterize_bwd")
         ck(_lib.dressi_transform_bwd(h, _p(self.mvp), B, V, _p(self.g_clip), _p(self.g_pos_t), s),
            "transform_bwd")
-        ck(_lib.dressi_vertex_attrs_bwd(h, _p(self.pos), _p(self.tris), V, T, Cv, _p(self.g_vattr),
-                                        _p(self.g_pos_t), _p(self.g_pos), s), "vertex_attrs_bwd")
+        ck(_lib.dressi_vertex_attrs_bwd(h, _p(self.pos), _p(self.tris), V, T, Cv, _p(self.adj),
+                                        _p(self.g_vattr), _p(self.g_pos_t), _p(self.g_pos), s),
+           "vertex_attrs_bwd")
 
     def run(self):
         """One full step: forward, loss and gradient, backward."""

@@ -335,3 +335,32 @@ def test_softras_hard_only_no_dist(B):
     assert (host(E) == 0).all()
     assert_vals_close(host(oc), oc_o)
     assert_vals_close(host(os_), os_o)
+
+
+def test_shared_index_and_adjacency_match_internal_builds(B):
+    """Passing a prebuilt fragment index and adjacency gives bitwise the same
+    gradients as letting each call build its own; the adjacency lists every
+    corner of every vertex in ascending order."""
+    pc, tris = sphere_scene(subdiv=4, views=2, seed=6)
+    V = int(tris.max()) + 1
+    H, W, K, r = 96, 80, 3, 0.04
+    tid, bary, dist = B.dressi_rasterize(dev(pc), dev(tris), H, W, K, r, 0)
+    adj = B.dressi_adjacency(dev(tris), V)
+    a = host(adj)
+    offs, corners = a[:V + 1], a[V + 1:]
+    assert offs[0] == 0 and offs[-1] == 3 * len(tris)
+    flat = tris.ravel()
+    for v in range(0, V, 97):
+        ref = np.nonzero(flat == v)[0]
+        assert np.array_equal(corners[offs[v]:offs[v + 1]], ref)
+    fi = B.dressi_fragment_index(tid, len(tris))
+    g = torch.randn_like(bary)
+    gd = torch.randn_like(dist)
+    g1 = host(B.dressi_rasterize_bwd(dev(pc), dev(tris), tid, g, gd, r))
+    g2 = host(B.dressi_rasterize_bwd(dev(pc), dev(tris), tid, g, gd, r, frag_index=fi, adj=adj))
+    assert np.array_equal(g1, g2)
+    attr = torch.randn((V, 7), device="cuda")
+    go = torch.randn(tid.shape + (7,), device="cuda")
+    a1, b1 = B.dressi_interpolate_bwd(attr, dev(tris), tid, bary, go)
+    a2, b2 = B.dressi_interpolate_bwd(attr, dev(tris), tid, bary, go, frag_index=fi, adj=adj)
+    assert np.array_equal(host(a1), host(a2)) and np.array_equal(host(b1), host(b2))

@@ -133,7 +133,7 @@ def _gpu_step(scene, views=None):
     return st
 
 
-def _compare_step(scene, views=None, env_tol=None, img_tol=1e-5):
+def _compare_step(scene, views=None, env_tol=None, img_tol=1e-5, kink_tol=False):
     st = _gpu_step(scene, views)
     o_st, o_tgt, o_g = ostep.step(scene, views)
     assert np.array_equal(host(st.tri_id), o_st["tid"]), "tri_id differs"
@@ -147,7 +147,19 @@ def _compare_step(scene, views=None, env_tol=None, img_tol=1e-5):
     if "color" in o_g:
         assert_grad_close(host(g["color"]), o_g["color"], what="grad colour")
     if "tex" in o_g:
-        assert_grad_close(host(g["tex"]), o_g["tex"], what="grad texture")
+        if kink_tol:
+            # The shading normal's gradient switches at n.l = 0 and r.v = 0
+            # (max(0, .) kinks); where those dot products are within rounding
+            # of 0 the two precisions can take different branches, which
+            # changes the normal-map texels fed by those pixels.  Norm-relative
+            # bar plus an element-wise bar on 99.99% of the texels.
+            gt, rt = host(g["tex"]).astype(np.float64), o_g["tex"]
+            rel = np.linalg.norm(gt - rt) / np.linalg.norm(rt)
+            assert rel <= 1e-4, f"grad texture rel {rel:.3e}"
+            ew = np.abs(gt - rt) / np.abs(rt).max()
+            assert np.quantile(ew, 0.9999) <= 1e-4, f"grad texture 99.99% elementwise {np.quantile(ew, 0.9999):.3e}"
+        else:
+            assert_grad_close(host(g["tex"]), o_g["tex"], what="grad texture")
     if "env" in o_g:
         ge, re = host(g["env"]), o_g["env"]
         rel = np.linalg.norm(ge - re) / np.linalg.norm(re)
@@ -171,7 +183,7 @@ def test_step_config3_two_views(B):
     # (normal map, normalisations, reflection, cube lookup) whose rounding is
     # amplified by the environment map's gradient: images get 5e-5 here.
     s = scenes.config3()
-    _compare_step(s, views=slice(0, 2), env_tol=2e-2, img_tol=5e-5)
+    _compare_step(s, views=slice(0, 2), env_tol=2e-2, img_tol=5e-5, kink_tol=True)
 
 
 def test_step_deterministic_and_graph_replay(B):
