@@ -39,6 +39,9 @@ def parse():
     ap.add_argument("--profile-steps", type=int, default=20)
     ap.add_argument("--only-graph", action="store_true",
                     help="only the captured-step replays (for external profilers)")
+    ap.add_argument("--no-multiview", dest="multiview", action="store_false",
+                    help="skip the 16-view batched-vs-plain measurement")
+    ap.add_argument("--multiview-steps", type=int, default=30)
     ap.add_argument("--copy-ref", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of MIB MiB (reference for HBM counters)")
     return ap.parse_args()
@@ -56,85 +59,166 @@ def scene_for(cfg):
 
 
 # ---------------------------------------------------------------------------
-# algorithmic bytes per launch of the main kernels (inputs read once and
-# outputs written once at their dtype; internal scratch is not counted)
+# Algorithmic bytes.  A tensor that crosses the library boundary (a stage's
+# input or output) is read once and written once at its dtype; a texture read
+# counts only the texels that can be touched, min(Ht*Wt, 4 * covered
+# fragments); each inverse-UV slice is cleared and read once in full and
+# written once per covered fragment.  Internal scratch (setup records, bins,
+# fragment index, per-tile partial sums) is not counted, so implementation
+# overhead shows up as a lower fraction of the roofline.
 # ---------------------------------------------------------------------------
-def kernel_bytes(name, st, cov):
-    B, K, H, W = st.B, st.K, st.H, st.W
-    N = B * K * H * W             # fragment slots
-    P = B * H * W                 # pixels
-    Nc = cov                      # covered fragments
-    V, T, Cv = st.V, st.T, st.Cv
-    soft = st.r > 0
+# HBM traffic per launch from two rocprofv3 counter runs of this script on the
+# headline workload (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch).  Each
+# counter is scaled by its reading for a plain 256 MiB device copy
+# (torch copy_, same runs): FETCH_SIZE read 131,085 KiB for 262,144 KiB moved
+# (x2.0), WRITE_SIZE 262,144 KiB (x1.0).  "sha" fingerprints the kernel's
+# source file when the counters were taken; the figure is reported as null
+# once that file has changed.
+FETCH_SCALE, WRITE_SCALE = 262144.0 / 131085.0, 1.0
+TRAFFIC = {
+    "k_invuv_gather": {"src": "paper_2204_01386_amd/csrc/texture.hip",
+                       "sha": "3f2328283ea81af892321598eb6a9939653658f915f731c33d3b38b03b4a59ed",
+                       "fetch_kib": 10125.8125, "write_kib": 16384.0},
+}
+
+
+def traffic_bytes(kernel):
+    t = TRAFFIC.get(kernel)
+    if t is None:
+        return None
+    import hashlib
+    with open(os.path.join(ROOT, t["src"]), "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != t["sha"]:
+            return None
+    return int(round((t["fetch_kib"] * FETCH_SCALE + t["write_kib"] * WRITE_SCALE) * 1024))
+
+
+class Shapes:
+    def __init__(self, st, cov):
+        self.B, self.K, self.H, self.W = st.B, st.K, st.H, st.W
+        self.N = st.B * st.K * st.H * st.W          # fragment slots
+        self.P = st.B * st.H * st.W                 # pixels
+        self.cov = cov                              # covered fragments
+        self.V, self.T, self.Cv = st.V, st.T, st.Cv
+        self.soft = st.r > 0
+        self.mode = st.mode
+        self.ex = st.extra is not None
+        self.Vuv = 0 if st.uv is None else st.uv.shape[0]
+        self.Ct = st.Ct
+        self.cells = 0 if st.tex is None else st.tex.shape[0] * st.tex.shape[1]
+        self.env = st.env is not None
+        self.ecells = 0 if st.env is None else st.env.shape[0] * st.env.shape[1] * st.env.shape[2]
+        self.S = st.B * st.K
+        self.adj = (st.V + 1 + 3 * st.T) * 4
+        self.uvadj = (self.Vuv + 1 + 3 * st.T) * 4
+
+    def touched(self, cells, C):
+        return min(cells, 4 * self.cov) * C * 4
+
+
+def call_bytes(z: Shapes):
+    """Algorithmic bytes of every library call of one step, by call."""
+    N, P, V, T, Cv, B = z.N, z.P, z.V, z.T, z.Cv, z.B
+    d = 4 if z.soft else 0
+    sh_in = N * 4 + N * 6 * 4 + (N * z.Ct * 4 if z.Ct else N * 12) + (N * 12 if z.env else 0) + B * 12
+    out = {
+        "vertex_attrs": V * 12 + T * 12 + z.adj + (V * 12 if z.ex else 0) + V * Cv * 4,
+        "transform": V * 12 + B * 64 + B * V * 16,
+        "rasterize": B * V * 16 + T * 12 + N * (4 + 8 + d),
+        "interpolate": V * Cv * 4 + T * 12 + N * 12 + N * Cv * 4,
+        "softras": N * (12 + 4 + d) + P * (12 + 4 + 1),
+        "loss_l2": P * (12 + 4 + 16) + P * 16,
+        "softras_bwd": N * (12 + 4 + d) + P * (1 + 12 + 4) + N * (12 + d),
+        "shade": sh_in + N * 12,
+        "shade_bwd": sh_in + N * 12 + N * 6 * 4 + (N * z.Ct * 4 if z.Ct else N * 12),
+        "interpolate_bwd": N * 12 + N * Cv * 4 + V * Cv * 4 + T * 12 + z.adj + N * 8 + V * Cv * 4,
+        "rasterize_bwd": B * V * 16 + T * 12 + z.adj + N * (4 + 8 + d) + B * V * 16,
+        "transform_bwd": B * V * 16 + B * 64 + V * 12,
+        "vertex_attrs_bwd": V * 12 + T * 12 + z.adj + V * Cv * 4 + V * 12 + V * 12,
+    }
+    if z.Ct:
+        out["interpolate uv"] = z.Vuv * 8 + T * 12 + N * 12 + N * 8
+        out["texture"] = N * 12 + z.touched(z.cells, z.Ct) + N * z.Ct * 4
+        out["interpolate_bwd uv"] = z.Vuv * 8 + T * 12 + N * 12 + N * 8 + N * 8 + N * 8
+        out["texture_bwd"] = (N * 12 + z.touched(z.cells, z.Ct) + N * z.Ct * 4 + N * 8
+                              + z.S * z.cells * 4 * 2 + z.cov * 4
+                              + min(z.cov, z.S * z.cells) * (8 + z.Ct * 4) + z.cells * z.Ct * 4)
+    if z.env:
+        out["shade dir"] = N * 4 + N * 12 * 3 + B * 12 + N * 12
+        out["texture env"] = N * 16 + z.touched(z.ecells, 3) + N * 12
+        out["shade_bwd env"] = sh_in + N * 12 + N * 12
+        out["texture_bwd env"] = (N * 16 + z.touched(z.ecells, 3) + N * 12 + N * 12
+                                  + z.S * z.ecells * 4 * 2 + z.cov * 4
+                                  + min(z.cov, z.S * z.ecells) * (12 + 12) + z.ecells * 12)
+    return out
+
+
+def kernel_bytes(name, z: Shapes):
+    """Algorithmic bytes per launch of a kernel (same accounting as above),
+    or None for kernels that only move internal scratch."""
+    N, P, V, T, Cv, B = z.N, z.P, z.V, z.T, z.Cv, z.B
+    d = 4 if z.soft else 0
     if name == "k_raster":
-        return N * (4 + 8 + (4 if soft else 0))
-    if name == "k_setup_count":
+        return N * (4 + 8 + d)
+    if name == "k_setup_bin":
         return B * V * 16 + T * 12
-    if name == "k_interp":
-        # one of the interpolations: the per-vertex attributes (Cv channels)
-        return N * (4 + 8) + N * 4 * Cv + V * Cv * 4 + T * 12
-    if name == "k_tex_fwd":
-        Ct = st.Ct
-        texels = min(st.tex.shape[0] * st.tex.shape[1], 4 * Nc)
-        return N * (4 + 8) + texels * Ct * 4 + N * Ct * 4
-    if name == "k_invuv_gather":
-        Ct = st.Ct
-        cells = st.tex.shape[0] * st.tex.shape[1]
-        S = B * K
-        return S * cells * 4 + cells * Ct * 4 + min(Nc, S * cells) * (8 + Ct * 4)
-    if name == "k_invuv_build":
-        S = B * K
-        cells = st.tex.shape[0] * st.tex.shape[1]
-        return N * (4 + 8) + min(Nc, S * cells) * 4
-    if name == "k_shade":
-        return N * 4 + N * 4 * (6 + st.Ct) + N * 12
-    if name == "k_shade_bwd":
-        return N * 4 + N * 4 * (6 + st.Ct) + N * 12 + N * 4 * (6 + st.Ct)
+    if name == "k_interp":        # per-vertex attributes and (textured) UVs: mean per launch
+        a = V * Cv * 4 + T * 12 + N * 12 + N * Cv * 4
+        if not z.Ct:
+            return a
+        return (a + z.Vuv * 8 + T * 12 + N * 12 + N * 8) // 2
+    if name == "k_tex_fwd":       # albedo (and environment) lookups: mean per launch
+        a = N * 12 + z.touched(z.cells, z.Ct) + N * z.Ct * 4
+        if not z.env:
+            return a
+        return (a + N * 16 + z.touched(z.ecells, 3) + N * 12) // 2
+    if name == "k_invuv_gather" and not z.env:
+        return z.S * z.cells * 4 + min(z.cov, z.S * z.cells) * (8 + z.Ct * 4) + z.cells * z.Ct * 4
+    if name == "k_tex_bwd_pixel" and not z.env:
+        return N * 12 + z.touched(z.cells, z.Ct) + N * z.Ct * 4 + N * 8 + z.cov * 4
     if name == "k_blend":
-        return N * (12 + 4 + (4 if soft else 0)) + P * (12 + 4 + 1)
+        return N * (12 + 4 + d) + P * (12 + 4 + 1)
     if name == "k_blend_bwd":
-        return N * (12 + 4 + (4 if soft else 0)) + P * (1 + 12 + 4) + N * (12 + (4 if soft else 0))
-    if name == "k_rast_bwd_tri":
-        return Nc * (8 + (4 if soft else 0)) + B * V * 16 + T * 12 + B * T * 36
-    if name == "k_interp_bwd_tri":
-        return Nc * (8 + 4 * Cv) + B * T * 3 * Cv * 4
-    if name == "k_interp_bwd_bary":
-        return N * 4 + N * 4 * Cv + N * 8
-    if name == "k_tex_bwd_coord":
-        Ct = st.Ct
-        texels = min(st.tex.shape[0] * st.tex.shape[1], 4 * Nc)
-        return N * (4 + 8) + texels * Ct * 4 + N * Ct * 4 + N * 8
-    if name == "k_fragsort":
-        return N * 4
+        return N * (12 + 4 + d) + P * (1 + 12 + 4) + N * (12 + d)
     if name == "k_loss_l2":
         return P * (12 + 4 + 16) + P * 16
+    if name == "k_interp_bwd_tile":
+        return N * 12 + N * Cv * 4 + V * Cv * 4 + T * 12 + (N * 8 if z.Ct else 0) + N * 8
+    if name == "k_interp_bwd_bary":
+        return z.Vuv * 8 + T * 12 + N * 12 + N * 8 + N * 8
+    if name == "k_interp_vertex_gather":
+        return z.adj + V * Cv * 4
+    if name == "k_rast_bwd_tile":
+        return B * V * 16 + T * 12 + N * (4 + 8 + d)
+    if name == "k_vertex_gather_pos":
+        return z.adj + B * V * 16
+    if name == "k_fragsort":
+        return N * 4
+    if name == "k_transform":
+        return V * 12 + B * 64 + B * V * 16
+    if name == "k_transform_bwd":
+        return B * V * 16 + B * 64 + V * 12
+    if name == "k_vertex_attrs":
+        return V * 12 + T * 12 + z.adj + (V * 12 if z.ex else 0) + V * Cv * 4
+    if name == "k_shade_bwd" and not z.env:
+        sh_in = N * 4 + N * 6 * 4 + (N * z.Ct * 4 if z.Ct else N * 12) + B * 12
+        return sh_in + N * 12 + N * 6 * 4 + (N * z.Ct * 4 if z.Ct else N * 12)
+    if name == "k_shade" and not z.env:
+        return N * 4 + N * 6 * 4 + (N * z.Ct * 4 if z.Ct else N * 12) + B * 12 + N * 12
     return None
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU only (one MI355X per box); --gpus {args.gpus} is not "
-              f"supported. The path shards by views/instances; see the design notes.", file=sys.stderr)
-        sys.exit(2)
+def measure(scene, steps, warmup, prof_steps, plain_steps_min=10):
+    """Times one scene: captured-graph replays ("batched"), eager per-view
+    calls ("plain"), and a per-kernel breakdown (one event pair per launch,
+    stamped from the kernel's own dispatch)."""
     import ctypes as C
 
-    import numpy as np
     import torch
 
     from paper_2204_01386_amd import binding as Bd
     from paper_2204_01386_amd.pipeline import Step, make_target
 
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
-    torch.cuda.set_device(0)
-    if args.copy_ref:
-        src = torch.ones(args.copy_ref * (1 << 18), dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-    scene, desc = scene_for(args.config)
     B = scene.mvp.shape[0]
     tgt = make_target(scene)
     st = Step(scene, target=tgt)
@@ -155,7 +239,7 @@ def main():
     torch.cuda.synchronize()
     with torch.cuda.graph(graph):
         st.run()
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         graph.replay()
     torch.cuda.synchronize()
 
@@ -164,17 +248,17 @@ def main():
     torch.cuda.synchronize()
     t_wall = time.perf_counter()
     e0.record()
-    for _ in range(args.steps):
+    for _ in range(steps):
         graph.replay()
     e1.record()
     torch.cuda.synchronize()
     t_wall = time.perf_counter() - t_wall
-    ms_batched = e0.elapsed_time(e1) / args.steps
-    if args.only_graph:
-        print(json.dumps({"ms_per_step": ms_batched}))
-        return
+    ms_batched = e0.elapsed_time(e1) / steps
     if ctx.check_status() != 0:
         raise SystemExit("tile-bin capacity overflow in the timed region")
+    res = {"ms_per_step": ms_batched, "wall_s_timed": t_wall, "graph": graph, "step": st}
+    if prof_steps < 0:
+        return res
 
     # ---- plain: eager calls, one view per call -----------------------------
     if B == 1:
@@ -187,40 +271,93 @@ def main():
         for ps in plain_steps:
             ps.run()
     torch.cuda.synchronize()
-    n_plain = max(10, args.steps // 4)
+    n_plain = max(plain_steps_min, steps // 4)
     e0.record()
     for _ in range(n_plain):
         for ps in plain_steps:
             ps.run()
     e1.record()
     torch.cuda.synchronize()
-    ms_plain = e0.elapsed_time(e1) / n_plain
+    res["plain_ms_per_step"] = e0.elapsed_time(e1) / n_plain
+    del plain_steps
 
-    # ---- per-kernel timing (HIP events around every launch, eager) ---------
-    n_prof = args.profile_steps
-    cap = 200 * n_prof
+    # ---- per-kernel timing ------------------------------------------------
+    cap = 400 * max(prof_steps, 1)
     Bd._lib.dressi_profile_start(cap)
-    for _ in range(n_prof):
+    for _ in range(prof_steps):
         st.run()
     torch.cuda.synchronize()
     names = (C.c_char_p * cap)()
     ms = (C.c_float * cap)()
     n = Bd._lib.dressi_profile_read(names, ms, cap)
     Bd._lib.dressi_profile_start(0)
+    if n < 0:
+        raise SystemExit(f"kernel profiler failed ({n})")
     per = {}
     for i in range(n):
         k = names[i].decode()
         tot, cnt = per.get(k, (0.0, 0))
         per[k] = (tot + ms[i], cnt + 1)
-    table = sorted(((k, tot / n_prof, tot / cnt, cnt // n_prof) for k, (tot, cnt) in per.items()),
-                   key=lambda x: -x[1])
-    cov = int((st.tri_id >= 0).sum().item())
-    dom = next((row for row in table if kernel_bytes(row[0], st, cov) is not None), table[0])
-    dom_bytes = kernel_bytes(dom[0], st, cov)
+    res["table"] = sorted(((k, tot / prof_steps, tot / cnt, cnt // prof_steps)
+                           for k, (tot, cnt) in per.items()), key=lambda x: -x[1])
+    res["cov"] = int((st.tri_id >= 0).sum().item())
+    return res
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (one MI355X per box); --gpus {args.gpus} is not "
+              f"supported. The path shards by views/instances; see the design notes.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    if args.copy_ref:
+        src = torch.ones(args.copy_ref * (1 << 18), dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    scene, desc = scene_for(args.config)
+    B = scene.mvp.shape[0]
+    m = measure(scene, args.steps, args.warmup, -1 if args.only_graph else args.profile_steps)
+    ms_batched = m["ms_per_step"]
+    if args.only_graph:
+        print(json.dumps({"ms_per_step": ms_batched}))
+        return
+    st, table, cov = m["step"], m["table"], m["cov"]
+    z = Shapes(st, cov)
+    step_bytes = sum(call_bytes(z).values())
+    dom = next((row for row in table if kernel_bytes(row[0], z) is not None), table[0])
+    dom_bytes = kernel_bytes(dom[0], z)
     achieved = dom_bytes / (dom[2] * 1e-3) / 1e9 if dom_bytes else None
     kernel_rows = [{"kernel": k, "ms_per_step": round(a, 5), "ms_per_launch": round(b, 5),
-                    "launches_per_step": c,
-                    "alg_bytes": kernel_bytes(k, st, cov)} for k, a, b, c in table]
+                    "launches_per_step": c, "alg_bytes": kernel_bytes(k, z)} for k, a, b, c in table]
+    ms_plain = m["plain_ms_per_step"]
+    del m
+
+    # ---- the 16-view batched configuration beside its per-view form -------
+    multi = None
+    if args.multiview and args.config != 3:
+        s3, d3 = scene_for(3)
+        m3 = measure(s3, args.multiview_steps, 5, args.profile_steps // 4, plain_steps_min=3)
+        z3 = Shapes(m3["step"], m3["cov"])
+        b3 = sum(call_bytes(z3).values())
+        pix3 = s3.mvp.shape[0] * s3.H * s3.W
+        multi = {"workload": d3, "views": int(s3.mvp.shape[0]),
+                 "ms_per_step": round(m3["ms_per_step"], 4),
+                 "value": round(pix3 / (m3["ms_per_step"] * 1e-3) / 1e6, 2), "unit": "Mpix/s",
+                 "tris_per_s": round(s3.mvp.shape[0] * s3.tris.shape[0] / (m3["ms_per_step"] * 1e-3), 1),
+                 "plain_ms_per_step": round(m3["plain_ms_per_step"], 4),
+                 "batched_vs_plain_speedup": round(m3["plain_ms_per_step"] / m3["ms_per_step"], 3),
+                 "step_alg_bytes": b3,
+                 "step_hbm_frac": round(b3 / (m3["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                 "kernels": [{"kernel": k, "ms_per_step": round(a, 5), "launches_per_step": c}
+                             for k, a, b, c in m3["table"][:12]]}
+        del m3
 
     # ---- CPU baseline: the oracle's step on the same workload --------------
     cpu = None
@@ -262,15 +399,17 @@ def main():
         "plain": {"ms_per_step": round(ms_plain, 5),
                   "value": round(pix / (ms_plain * 1e-3) / 1e6, 3), "unit": "Mpix/s"},
         "batched_vs_plain_speedup": round(ms_plain / ms_batched, 3),
-        "wall_s_timed": round(t_wall, 4),
+        "step_alg_bytes": step_bytes,
+        "step_hbm_frac": round(step_bytes / (ms_batched * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "roofline": {"bound": "hbm", "kernel": dom[0],
                      "achieved": round(achieved, 2) if achieved else None,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
-                     "traffic": None,
+                     "traffic": traffic_bytes(dom[0]),
                      "alg_bytes_per_launch": dom_bytes,
                      "ms_per_launch": round(dom[2], 5)},
         "cpu_baseline": cpu,
+        "multiview": multi,
         "kernels": kernel_rows,
     }
     print(json.dumps(res))

@@ -154,16 +154,13 @@ void prof_free() {
 }
 }  // namespace
 
-int dr_prof_begin(const char *name, hipStream_t s) {
-    if (!g_prof.on || g_prof.used >= g_prof.cap) return -1;
+bool dr_prof_slot(const char *name, hipEvent_t *start, hipEvent_t *stop) {
+    if (!g_prof.on || g_prof.used >= g_prof.cap) return false;
     int i = g_prof.used++;
     g_prof.names[i] = name;
-    (void)hipEventRecord(g_prof.ev[2 * i], s);
-    return i;
-}
-
-void dr_prof_end(int slot, hipStream_t s) {
-    if (slot >= 0) (void)hipEventRecord(g_prof.ev[2 * slot + 1], s);
+    *start = g_prof.ev[2 * i];
+    *stop = g_prof.ev[2 * i + 1];
+    return true;
 }
 
 extern "C" int dressi_profile_start(int max_launches) {

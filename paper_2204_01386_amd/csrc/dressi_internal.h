@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <cstdint>
 #include <string>
@@ -40,15 +41,20 @@ int dressi_launch_check(dressi_ctx *ctx, const char *what);
 int dressi_counters(dressi_ctx *ctx, size_t n, hipStream_t stream);
 
 // Optional per-kernel timing with HIP events (eager runs only): every launch
-// goes through DR_LAUNCH, which brackets it with event records while the
-// profiler is on (dressi_profile_start) and costs one branch otherwise.
-int dr_prof_begin(const char *name, hipStream_t s);
-void dr_prof_end(int slot, hipStream_t s);
+// goes through DR_LAUNCH.  While the profiler is on (dressi_profile_start) the
+// launch takes a start/stop event pair that the runtime stamps from the
+// kernel's own dispatch (hipExtLaunchKernelGGL), so the measured time is the
+// kernel's execution alone; otherwise it costs one branch.
+bool dr_prof_slot(const char *name, hipEvent_t *start, hipEvent_t *stop);
 #define DR_LAUNCH(NAME, KERN, GRID, BLOCK, SHMEM, STREAM, ...)                  \
     do {                                                                        \
-        int dr_ps_ = dr_prof_begin(NAME, STREAM);                               \
-        hipLaunchKernelGGL(KERN, dim3(GRID), dim3(BLOCK), SHMEM, STREAM, __VA_ARGS__); \
-        dr_prof_end(dr_ps_, STREAM);                                            \
+        hipEvent_t dr_e0_ = nullptr, dr_e1_ = nullptr;                          \
+        if (dr_prof_slot(NAME, &dr_e0_, &dr_e1_))                               \
+            hipExtLaunchKernelGGL(KERN, dim3(GRID), dim3(BLOCK), SHMEM, STREAM, \
+                                  dr_e0_, dr_e1_, 0, __VA_ARGS__);              \
+        else                                                                    \
+            hipLaunchKernelGGL(KERN, dim3(GRID), dim3(BLOCK), SHMEM, STREAM,    \
+                               __VA_ARGS__);                                    \
     } while (0)
 
 // Bump allocator over the arena: carve(n) returns 256-byte aligned offsets.
@@ -134,8 +140,13 @@ struct TriSetup {
     float Af;         // twice the area as float
     int meta;         // bit0 valid, bits1-3 edge owns zero, bits 4-9 corner of vertex i
     int box0, box1;   // pixel bbox: x0 | x1 << 16, y0 | y1 << 16 (hard or soft)
+    // for the soft rasterizer's culling tests
+    int hbox0, hbox1; // pixels whose centres lie in the vertex box, as box0/box1 (signed halves)
+    int zlb;          // float bits of a lower bound of the hard keys (>= 0)
+    float il[3];      // 1 / edge length (fixed-point units), edge i opposite vertex i
+    int pad[2];
 };
-static_assert(sizeof(TriSetup) == 64, "setup record is one 64-byte line");
+static_assert(sizeof(TriSetup) == 96, "setup record is 96 bytes");
 
 __device__ __forceinline__ bool dr_snap(float c, float w, float half, bool is_y, int &out) {
     float n = c / w;
@@ -156,6 +167,10 @@ __device__ __forceinline__ TriSetup dr_setup(const float4 *pc, int v0, int v1, i
     s.meta = 0;
     s.box0 = 1;      // empty box (x0 = 1 > x1 = 0)
     s.box1 = 1;
+    s.hbox0 = s.hbox1 = 1;
+    s.zlb = 0;
+    s.il[0] = s.il[1] = s.il[2] = 0.0f;
+    s.pad[0] = s.pad[1] = 0;
     const int vid[3] = {v0, v1, v2};
     float4 p[3];
     int X[3], Y[3];
@@ -198,6 +213,22 @@ __device__ __forceinline__ TriSetup dr_setup(const float4 *pc, int v0, int v1, i
     int x1 = floor_div256(xmax - 128) + margin;
     int y0 = -floor_div256(-(ymin - 128)) - margin;
     int y1 = floor_div256(ymax - 128) + margin;
+    {
+        int hx0 = x0 + margin, hx1 = x1 - margin, hy0 = y0 + margin, hy1 = y1 - margin;
+        hx0 = min(max(hx0, -1), W); hx1 = min(max(hx1, -1), W);
+        hy0 = min(max(hy0, -1), H); hy1 = min(max(hy1, -1), H);
+        s.hbox0 = (hx0 & 0xffff) | (hx1 << 16);
+        s.hbox1 = (hy0 & 0xffff) | (hy1 << 16);
+        float zmin = fminf(fminf(s.zn[0], s.zn[1]), s.zn[2]);
+        float zlb = 0.5f * zmin - 1e-6f;
+        s.zlb = zlb > 0.0f ? __float_as_int(zlb) : 0;
+#pragma unroll
+        for (int i = 0; i < 3; i++) {
+            int a = (i + 1) % 3, c = (i + 2) % 3;
+            float ex = (float)(s.X[c] - s.X[a]), ey = (float)(s.Y[c] - s.Y[a]);
+            s.il[i] = 1.0f / sqrtf(ex * ex + ey * ey);
+        }
+    }
     x0 = max(x0, 0); y0 = max(y0, 0);
     x1 = min(x1, W - 1); y1 = min(y1, H - 1);
     if (x0 > x1 || y0 > y1) return s;
@@ -209,36 +240,45 @@ __device__ __forceinline__ TriSetup dr_setup(const float4 *pc, int v0, int v1, i
 
 __device__ __forceinline__ int dr_corner(int meta, int i) { return (meta >> (4 + 2 * i)) & 3; }
 
+// Integer products in double.  Snapped coordinates satisfy |X|, |Y| < 2^22
+// and pixel centres are below 2^23, so every difference is below 2^24, every
+// product or sum of two products below 2^49: all exact in a double's 53-bit
+// significand.  The results (and their conversions to float) are therefore the
+// same as with 64-bit integers, at FP64 FMA rate instead of emulated 64-bit
+// integer multiplies.
+//
 // Edge function of the edge opposite vertex i at fixed-point (px, py).
-__device__ __forceinline__ int64_t dr_edge(const int *X, const int *Y, int i, int px, int py) {
+__device__ __forceinline__ double dr_edge(const int *X, const int *Y, int i, int px, int py) {
     int a = (i == 2) ? 0 : i + 1;
     int b = (i == 0) ? 2 : i - 1;
-    return (int64_t)(X[b] - X[a]) * (int64_t)(py - Y[a]) -
-           (int64_t)(Y[b] - Y[a]) * (int64_t)(px - X[a]);
+    double ex = (double)(X[b] - X[a]), ey = (double)(Y[b] - Y[a]);
+    double qx = (double)(px - X[a]), qy = (double)(py - Y[a]);
+    return ex * qy - ey * qx;
 }
 
 // Segment distance (fixed-point units, float) of edge i, from exact integers.
+template <typename TE>
 __device__ __forceinline__ float dr_segdist(const int *X, const int *Y, int i, int px, int py,
-                                            int64_t E) {
+                                            TE E) {
     int a = (i == 2) ? 0 : i + 1;
     int b = (i == 0) ? 2 : i - 1;
-    int64_t ex = X[b] - X[a], ey = Y[b] - Y[a];
-    int64_t qx = px - X[a], qy = py - Y[a];
-    int64_t dot = qx * ex + qy * ey;
-    int64_t len2 = ex * ex + ey * ey;
-    if (dot <= 0) return sqrtf((float)(qx * qx + qy * qy));
+    double ex = (double)(X[b] - X[a]), ey = (double)(Y[b] - Y[a]);
+    double qx = (double)(px - X[a]), qy = (double)(py - Y[a]);
+    double dot = qx * ex + qy * ey;
+    double len2 = ex * ex + ey * ey;
+    if (dot <= 0.0) return sqrtf((float)(qx * qx + qy * qy));
     if (dot >= len2) {
-        int64_t rx = px - X[b], ry = py - Y[b];
+        double rx = (double)(px - X[b]), ry = (double)(py - Y[b]);
         return sqrtf((float)(rx * rx + ry * ry));
     }
-    int64_t ae = E < 0 ? -E : E;
-    return (float)ae / sqrtf((float)len2);
+    return (float)(E < 0 ? -E : E) / sqrtf((float)len2);
 }
 
 // Normalised distance (pixels / W) to the triangle and the nearest edge
 // (lowest index on ties).
+template <typename TE>
 __device__ __forceinline__ float dr_distnorm(const int *X, const int *Y, int px, int py,
-                                             const int64_t *E, float scale, int &nearest) {
+                                             const TE *E, float scale, int &nearest) {
     float best = dr_segdist(X, Y, 0, px, py, E[0]);
     nearest = 0;
     float d1 = dr_segdist(X, Y, 1, px, py, E[1]);
@@ -248,7 +288,8 @@ __device__ __forceinline__ float dr_distnorm(const int *X, const int *Y, int px,
     return best / scale;
 }
 
-__device__ __forceinline__ float dr_depth(const TriSetup &s, const int64_t *E) {
+template <typename TE>
+__device__ __forceinline__ float dr_depth(const TriSetup &s, const TE *E) {
     float l1 = (float)E[1] / s.Af;
     float l2 = (float)E[2] / s.Af;
     float d1 = s.zn[1] - s.zn[0];

@@ -1,19 +1,22 @@
 // Rasterization forward and backward for gfx950.
 //
 // Forward (Algorithm 2 and the Shift equation of §3.4.2, depth peeling with K
-// buffers): triangle setup -> per-tile counts -> scan -> bin fill -> tile
-// rasterizer.  A 16x16 tile is one 256-lane workgroup, one lane per pixel.
-// Triangle records of the tile's bin are staged through LDS 256 at a time and
-// every lane keeps its K best (distinct key, smallest id) fragments in
-// registers, which is what K passes of depth peeling with a LESS depth test
-// select; the list is order independent, so bin order does not matter.
+// buffers): one kernel sets up every triangle (snap to 8 sub-pixel bits,
+// orientation, top-left ownership, box) and appends it to the fixed-capacity
+// bins of the 16x16 tiles its box covers; one workgroup per tile then
+// rasterizes.  Hard rasterization (r = 0) is triangle-parallel: each lane
+// walks one binned triangle's pixels in the tile and merges its fragments
+// into per-pixel LDS slots with 64-bit atomicMin, K passes for K layers.  Soft
+// rasterization (r > 0) is pixel-parallel: each lane keeps its pixel's K best
+// fragments in registers while the tile's triangles stream through LDS.  Both
+// select, independently of the visiting order, the K smallest distinct keys
+// with the smallest triangle id at each key.
 //
 // Backward: the fragments of every tile are sorted by triangle id in LDS
-// (bitonic sort); one thread per triangle then walks its fragments in the
-// tiles its box covers (binary search in each tile's sorted record list),
-// accumulating vertex gradients in registers, and one thread per vertex sums
-// its corners in ascending order.  No float atomics: results are bitwise
-// reproducible.
+// (bitonic sort) into per-tile records; per-record sums of the screen-space
+// vertex gradients are formed in LDS, summed per triangle over the tiles it
+// touches in a fixed order, and gathered per vertex over its corners in
+// ascending order.  No float atomics: results are bitwise reproducible.
 #include "dressi_internal.h"
 
 #include <algorithm>
@@ -55,6 +58,7 @@ __global__ void k_setup_bin(const float4 *__restrict__ pos_clip, const int32_t *
         if (v0 < 0 || v0 >= V || v1 < 0 || v1 >= V || v2 < 0 || v2 >= V) {
             s.meta = 0;
             s.box0 = s.box1 = 1;
+            s.hbox0 = s.hbox1 = 1;
         } else {
             s = dr_setup(pos_clip + (int64_t)b * V, v0, v1, v2, H, W, cull, margin);
         }
@@ -130,7 +134,7 @@ __device__ __forceinline__ void raster_tri_in_tile(const TriSetup &s, int t, int
         const int py = DRESSI_SUBPIX * y + DRESSI_SUBPIX / 2;
         for (int x = x0; x <= x1; x++) {
             const int px = DRESSI_SUBPIX * x + DRESSI_SUBPIX / 2;
-            int64_t E[3];
+            double E[3];
             bool in = true;
 #pragma unroll
             for (int i = 0; i < 3; i++) {
@@ -155,6 +159,48 @@ __device__ __forceinline__ void raster_tri_in_tile(const TriSetup &s, int t, int
             if (!(key > prev[p])) continue;
             unsigned long long v = ((unsigned long long)__float_as_uint(key) << 32) | (unsigned)t;
             atomicMin(&slot[p], v);
+        }
+    }
+}
+
+// Writes the K layers of one pixel: triangle id, perspective-correct (b0, b1)
+// and, for soft rasterization, the signed normalised distance (+ for a hard
+// fragment, - for a soft one).
+template <int K, bool SOFT>
+__device__ __forceinline__ void resolve_store(const TriSetup *__restrict__ sv, const float *key,
+                                              const int *id, int b, int x, int y, int px, int py,
+                                              int H, int W, float dscale, int32_t *__restrict__ tri_id,
+                                              float2 *__restrict__ bary, float *__restrict__ dist) {
+    if (x >= W || y >= H) return;
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+        int64_t o = (((int64_t)b * K + k) * H + y) * W + x;
+        int t = id[k];
+        if (t < 0) {
+            tri_id[o] = -1;
+            bary[o] = make_float2(0.0f, 0.0f);
+            if (SOFT) dist[o] = 0.0f;
+            continue;
+        }
+        TriSetup s = sv[t];
+        double E[3];
+#pragma unroll
+        for (int i = 0; i < 3; i++) E[i] = dr_edge(s.X, s.Y, i, px, py);
+        // perspective division in double: soft fragments extrapolate and the
+        // sum of l_i/w_i can come close to zero for grazing triangles
+        const double A2 = (double)s.Af;
+        double q0 = ((double)E[0] / A2) / (double)s.w[0];
+        double q1 = ((double)E[1] / A2) / (double)s.w[1];
+        double q2 = ((double)E[2] / A2) / (double)s.w[2];
+        double Q = q0 + q1 + q2;
+        double b0 = q0 / Q, b1 = q1 / Q, b2 = q2 / Q;
+        bool swapped = dr_corner(s.meta, 1) == 2;
+        tri_id[o] = t;
+        bary[o] = make_float2((float)b0, (float)(swapped ? b2 : b1));
+        if (SOFT) {
+            int ne;
+            float dn = dr_distnorm(s.X, s.Y, px, py, E, dscale, ne);
+            dist[o] = key[k] < 0.5f ? dn : -dn;
         }
     }
 }
@@ -208,38 +254,257 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX)
         __syncthreads();
     }
     if (p == 0) counts[bt] = 0;   // every lane has read it before the first barrier
-    if (x >= W || y >= H) return;
+    resolve_store<K, SOFT>(sv, key, id, b, x, y, px, py, H, W, dscale, tri_id, bary, dist);
+}
+
+// ---------------------------------------------------------------------------
+// soft rasterizer (r > 0): one 16x16 tile per workgroup, one lane per pixel,
+// each wavefront a 16x4 strip.  Each lane keeps its pixel's list of the K
+// smallest distinct keys (smallest id at each key), sorted in registers: one
+// pass over the tile's triangles selects exactly what K passes of depth
+// peeling select, with no atomics.  A soft reach of several pixels gives every
+// binned triangle many candidate pixels in the tile, which suits
+// pixel-parallel evaluation.
+//
+// The tile's bin is staged through LDS, 256 triangles at a time, with the
+// per-tile data the tests need.  A wavefront then tests 64 staged triangles at
+// once (one per lane) and evaluates only the survivors, one at a time across
+// its 64 pixels.  The bin is walked three times, nearest triangles first, so
+// that the lists fill with near fragments early and cull more of the rest:
+// (0) triangles whose vertex box covers pixel centres of the strip, (1) those
+// at most RL_NEAR pixels away, (2) the others.  Every culling test is exact by
+// construction (bounds carry rounding margins):
+//  * the soft box misses the strip;
+//  * the smallest key the triangle can give the strip (half its lowest vertex
+//    depth in walk 0, else the soft key of the L-infinity pixel gap between
+//    its vertex box and the strip) is above every lane's current K-th key;
+//  * per lane, a soft candidate is dropped before its segment distances when
+//    the line distance of an edge it lies outside of already rules it out.
+// Edge functions are evaluated in float with two FMAs per edge when staging
+// has shown that every value over the tile is an integer below 2^24 (then the
+// float result is exact); otherwise in the exact double form.
+// ---------------------------------------------------------------------------
+#define RL_BATCH 256
+#define RL_NEAR 2
+
+__device__ __forceinline__ float wave_max(float v) {
 #pragma unroll
-    for (int k = 0; k < K; k++) {
-        int64_t o = (((int64_t)b * K + k) * H + y) * W + x;
-        int t = id[k];
-        if (t < 0) {
-            tri_id[o] = -1;
-            bary[o] = make_float2(0.0f, 0.0f);
-            if (SOFT) dist[o] = 0.0f;
-            continue;
-        }
-        TriSetup s = sv[t];
-        int64_t E[3];
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+__device__ __forceinline__ int lo16(int v) { return (int)(short)(v & 0xffff); }
+__device__ __forceinline__ int hi16(int v) { return v >> 16; }
+
+// Merges the candidate fragment of triangle t at this lane's pixel.  MAYHARD
+// is false when no pixel centre of the wavefront can be inside the triangle.
+template <int K, bool MAYHARD, typename TE>
+__device__ __forceinline__ void rl_merge(const TriSetup &s, const TE *E, const float *il, int t, int px,
+                                         int py, float dscale, float r, float reach, float *key, int *id) {
+    bool in = MAYHARD;
+    if (MAYHARD) {
 #pragma unroll
-        for (int i = 0; i < 3; i++) E[i] = dr_edge(s.X, s.Y, i, px, py);
-        // perspective division in double: soft fragments extrapolate and the
-        // sum of l_i/w_i can come close to zero for grazing triangles
-        const double A2 = (double)s.Af;
-        double q0 = ((double)E[0] / A2) / (double)s.w[0];
-        double q1 = ((double)E[1] / A2) / (double)s.w[1];
-        double q2 = ((double)E[2] / A2) / (double)s.w[2];
-        double Q = q0 + q1 + q2;
-        double b0 = q0 / Q, b1 = q1 / Q, b2 = q2 / Q;
-        bool swapped = dr_corner(s.meta, 1) == 2;
-        tri_id[o] = t;
-        bary[o] = make_float2((float)b0, (float)(swapped ? b2 : b1));
-        if (SOFT) {
-            int ne;
-            float dn = dr_distnorm(s.X, s.Y, px, py, E, dscale, ne);
-            dist[o] = key[k] < 0.5f ? dn : -dn;
+        for (int i = 0; i < 3; i++) {
+            bool own = (s.meta >> (1 + i)) & 1;
+            in = in && (E[i] > 0 || (E[i] == 0 && own));
         }
     }
+    float kf;
+    if (in) {
+        float z = dr_depth(s, E);
+        if (!(z > 0.0f && z < 1.0f)) return;
+        kf = 0.5f * z;
+    } else {
+        // The distance to the triangle is at least the distance to the line
+        // of any edge the pixel lies outside of.  A soft fragment enters the
+        // list only if its key 0.5 + dn/2 is at most the list's last key, so
+        // it needs dn <= 2 (last - 0.5) (+ one rounding of the key) and
+        // dn <= r.  The bound is compared with a relative margin far above the
+        // float rounding of either side, so every fragment dropped here would
+        // also fail the exact tests below.
+        float ld = 0.0f;
+        if (E[0] < 0) ld = fmaxf(ld, (float)(-E[0]) * il[0]);
+        if (E[1] < 0) ld = fmaxf(ld, (float)(-E[1]) * il[1]);
+        if (E[2] < 0) ld = fmaxf(ld, (float)(-E[2]) * il[2]);
+        const float lim = fminf(reach, (2.0f * (key[K - 1] - 0.5f) + 2.4e-7f) * dscale * 1.001f);
+        if (ld > lim) return;
+        int ne;
+        float dn = dr_distnorm(s.X, s.Y, px, py, E, dscale, ne);
+        if (!(dn <= r)) return;
+        float h = 0.5f * dn;
+        kf = h + 0.5f;
+    }
+    if (!(kf <= key[K - 1])) return;
+    bool same = false;
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+        if (kf == key[k]) {
+            id[k] = min(id[k], t);
+            same = true;
+        }
+    }
+    if (same) return;
+    // insert below the first larger key; the largest entry drops out
+#pragma unroll
+    for (int k = K - 1; k > 0; k--) {
+        if (kf < key[k - 1]) {
+            key[k] = key[k - 1];
+            id[k] = id[k - 1];
+        } else if (kf < key[k]) {
+            key[k] = kf;
+            id[k] = t;
+        }
+    }
+    if (kf < key[0]) {
+        key[0] = kf;
+        id[0] = t;
+    }
+}
+
+template <int K>
+__global__ void __launch_bounds__(DRESSI_TILE_PIX)
+    k_raster_list(const TriSetup *__restrict__ setup, int32_t *__restrict__ counts,
+                  const int32_t *__restrict__ bins, int cap, int T, int H, int W, int ntx, int nt,
+                  float r, int32_t *__restrict__ tri_id, float2 *__restrict__ bary,
+                  float *__restrict__ dist) {
+    // staged triangles (structure of arrays)
+    __shared__ int sid[RL_BATCH];       // triangle id
+    __shared__ int sflag[RL_BATCH];     // meta | float-exact flag << 16
+    __shared__ int2 sbox[RL_BATCH];     // soft box
+    __shared__ int2 shb[RL_BATCH];      // pixels with centres in the vertex box
+    __shared__ int szlb[RL_BATCH];      // lower bound of the hard keys (float bits)
+    __shared__ float4 se[3][RL_BATCH];  // per edge: E at the tile's first pixel, 256 ex, 256 ey, 1/|e|
+    __shared__ int4 sxy0[RL_BATCH];     // X0 X1 X2 Y0
+    __shared__ int2 sxy1[RL_BATCH];     // Y1 Y2
+    __shared__ float4 sz[RL_BATCH];     // zn0 zn1 zn2 Af
+    const int bt = blockIdx.x;
+    const int b = bt / nt, tile = bt - b * nt;
+    const int tx = tile % ntx, ty = tile / ntx;
+    const int p = threadIdx.x;
+    const int lane = p & 63;
+    const int lx = p & (DRESSI_TILE - 1), ly = p / DRESSI_TILE;
+    const int x = tx * DRESSI_TILE + lx;
+    const int y = ty * DRESSI_TILE + ly;
+    const int px = DRESSI_SUBPIX * x + DRESSI_SUBPIX / 2;
+    const int py = DRESSI_SUBPIX * y + DRESSI_SUBPIX / 2;
+    const float flx = (float)lx, fly = (float)ly;
+    const float dscale = (float)W * 256.0f;
+    const float reach = r * dscale * 1.001f;   // conservative, in fixed-point units
+    const TriSetup *__restrict__ sv = setup + (int64_t)b * T;
+    const int32_t *__restrict__ bin = bins + (int64_t)bt * cap;
+    // this lane's wavefront: pixels [wx0, wx1] x [wy0, wy1]
+    const int wx0 = tx * DRESSI_TILE, wx1 = wx0 + DRESSI_TILE - 1;
+    const int wy0 = ty * DRESSI_TILE + (p / 64) * (64 / DRESSI_TILE);
+    const int wy1 = wy0 + 64 / DRESSI_TILE - 1;
+    const int px0 = DRESSI_SUBPIX * wx0 + DRESSI_SUBPIX / 2;                 // tile's first pixel centre
+    const int py0 = DRESSI_SUBPIX * (ty * DRESSI_TILE) + DRESSI_SUBPIX / 2;
+    int nbin = counts[bt];
+    if (nbin > cap) nbin = cap;
+
+    float key[K];
+    int id[K];
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+        key[k] = 2.0f;   // empty: above every fragment key
+        id[k] = -1;
+    }
+    int wmax_bits = __float_as_int(2.0f);   // bound on the strip's K-th keys (they only decrease)
+    int gap_max = 0x3fffffff;               // soft-only triangles farther (pixels) than this are culled
+
+    for (int walk = 0; walk < 3; walk++) {
+        for (int c0 = 0; c0 < nbin; c0 += RL_BATCH) {
+            const int n = min(RL_BATCH, nbin - c0);
+            if (walk == 0 || nbin > RL_BATCH) {   // a single batch stays staged
+                __syncthreads();
+                if (p < n) {
+                    const int t = bin[c0 + p];
+                    const TriSetup s = sv[t];
+                    bool fast = true;
+#pragma unroll
+                    for (int i = 0; i < 3; i++) {
+                        const int a = (i + 1) % 3, c = (i + 2) % 3;
+                        const int ex = s.X[c] - s.X[a], ey = s.Y[c] - s.Y[a];
+                        const double e0 = (double)ex * (double)(py0 - s.Y[a]) - (double)ey * (double)(px0 - s.X[a]);
+                        // E is affine: its extremes over the tile are at the corner pixels
+                        const double dx = (double)(DRESSI_SUBPIX * (DRESSI_TILE - 1)) * (double)ey;
+                        const double dy = (double)(DRESSI_SUBPIX * (DRESSI_TILE - 1)) * (double)ex;
+                        const double m = fmax(fmax(fabs(e0), fabs(e0 - dx)), fmax(fabs(e0 + dy), fabs(e0 + dy - dx)));
+                        fast = fast && m < 16777216.0;
+                        se[i][p] = make_float4((float)e0, 256.0f * (float)ex, 256.0f * (float)ey, s.il[i]);
+                    }
+                    sid[p] = t;
+                    sflag[p] = (s.meta & 0xffff) | (fast ? 0x10000 : 0);
+                    sbox[p] = make_int2(s.box0, s.box1);
+                    shb[p] = make_int2(s.hbox0, s.hbox1);
+                    szlb[p] = s.zlb;
+                    sxy0[p] = make_int4(s.X[0], s.X[1], s.X[2], s.Y[0]);
+                    sxy1[p] = make_int2(s.Y[1], s.Y[2]);
+                    sz[p] = make_float4(s.zn[0], s.zn[1], s.zn[2], s.Af);
+                }
+                __syncthreads();
+            }
+            for (int c = 0; c < n; c += 64) {
+                // 64 triangles tested at once, one per lane
+                const int e = c + lane;
+                bool want = false;
+                if (e < n) {
+                    const int2 bx = sbox[e];
+                    const bool hit = !(hi16(bx.x) < wx0 || (bx.x & 0xffff) > wx1 || hi16(bx.y) < wy0 ||
+                                       (bx.y & 0xffff) > wy1);
+                    const int2 hb = shb[e];
+                    const int gx = max(max(lo16(hb.x) - wx1, wx0 - hi16(hb.x)), 0);
+                    const int gy = max(max(lo16(hb.y) - wy1, wy0 - hi16(hb.y)), 0);
+                    const int g = max(gx, gy);
+                    if (walk == 0) want = hit && g == 0 && szlb[e] <= wmax_bits;
+                    else if (walk == 1) want = hit && g > 0 && g <= RL_NEAR && g <= gap_max;
+                    else want = hit && g > RL_NEAR && g <= gap_max;
+                }
+                unsigned long long todo = __ballot(want);
+                while (todo) {
+                    const int j = c + __ffsll((long long)todo) - 1;
+                    todo &= todo - 1ull;
+                    const int fl = sflag[j];
+                    const int t = sid[j];
+                    const float4 e0 = se[0][j], e1 = se[1][j], e2 = se[2][j];
+                    const int4 q0 = sxy0[j];
+                    const int2 q1 = sxy1[j];
+                    const float4 z4 = sz[j];
+                    TriSetup s;
+                    s.X[0] = q0.x; s.X[1] = q0.y; s.X[2] = q0.z;
+                    s.Y[0] = q0.w; s.Y[1] = q1.x; s.Y[2] = q1.y;
+                    s.zn[0] = z4.x; s.zn[1] = z4.y; s.zn[2] = z4.z;
+                    s.Af = z4.w;
+                    s.meta = fl & 0xffff;
+                    const float il[3] = {e0.w, e1.w, e2.w};
+                    if (fl >> 16) {
+                        // exact: every partial result is an integer below 2^24
+                        float E[3];
+                        E[0] = fmaf(e0.y, fly, fmaf(-e0.z, flx, e0.x));
+                        E[1] = fmaf(e1.y, fly, fmaf(-e1.z, flx, e1.x));
+                        E[2] = fmaf(e2.y, fly, fmaf(-e2.z, flx, e2.x));
+                        if (walk == 0) rl_merge<K, true>(s, E, il, t, px, py, dscale, r, reach, key, id);
+                        else rl_merge<K, false>(s, E, il, t, px, py, dscale, r, reach, key, id);
+                    } else {
+                        double E[3];
+#pragma unroll
+                        for (int i = 0; i < 3; i++) E[i] = dr_edge(s.X, s.Y, i, px, py);
+                        if (walk == 0) rl_merge<K, true>(s, E, il, t, px, py, dscale, r, reach, key, id);
+                        else rl_merge<K, false>(s, E, il, t, px, py, dscale, r, reach, key, id);
+                    }
+                }
+                // keys only decrease: refresh the strip's bounds
+                const float wm = wave_max(key[K - 1]);
+                wmax_bits = __float_as_int(wm);
+                // a soft candidate needs dn <= 2 (wmax - 0.5) + one key rounding;
+                // a pixel gap g (L-infinity, whole pixels) gives dn > (g - 1) / W
+                const float dp = (2.0f * (wm - 0.5f) + 1e-7f) * (float)W * 1.001f;
+                gap_max = (int)floorf(fminf(dp, 1.0e9f)) + 1;
+            }
+        }
+    }
+    __syncthreads();
+    if (p == 0) counts[bt] = 0;   // every lane has read it before the first barrier
+    resolve_store<K, true>(sv, key, id, b, x, y, px, py, H, W, dscale, tri_id, bary, dist);
 }
 
 template <int K>
@@ -247,8 +512,8 @@ static void launch_raster_k(bool soft, dim3 g, hipStream_t st, const TriSetup *s
                             const int32_t *bins, int cap, int T, int H, int W, int ntx, int nt, float r,
                             int32_t *tid, float2 *bary, float *dist) {
     if (soft)
-        DR_LAUNCH("k_raster", (k_raster<K, true>), g, DRESSI_TILE_PIX, 0, st, setup, counts, bins, cap, T, H,
-                  W, ntx, nt, r, tid, bary, dist);
+        DR_LAUNCH("k_raster_list", (k_raster_list<K>), g, DRESSI_TILE_PIX, 0, st, setup, counts, bins, cap, T,
+                  H, W, ntx, nt, r, tid, bary, dist);
     else
         DR_LAUNCH("k_raster", (k_raster<K, false>), g, DRESSI_TILE_PIX, 0, st, setup, counts, bins, cap, T, H,
                   W, ntx, nt, r, tid, bary, dist);
@@ -585,7 +850,7 @@ __device__ __forceinline__ void frag_range(const FragLists &fl, int64_t bt, int6
 __device__ __forceinline__ void rast_frag_grad(const TriSetup &s, int x, int y, float2 g2, float gdist,
                                                bool want_dist, int W, float *out) {
     const int px = DRESSI_SUBPIX * x + DRESSI_SUBPIX / 2, py = DRESSI_SUBPIX * y + DRESSI_SUBPIX / 2;
-    int64_t E[3];
+    double E[3];
     bool in = true;
 #pragma unroll
     for (int i = 0; i < 3; i++) {
