@@ -143,7 +143,7 @@ struct TriSetup {
     // for the soft rasterizer's culling tests
     int hbox0, hbox1; // pixels whose centres lie in the vertex box, as box0/box1 (signed halves)
     int zlb;          // float bits of a lower bound of the hard keys (>= 0)
-    float il[3];      // 1 / edge length (fixed-point units), edge i opposite vertex i
+    float elen[3];    // sqrtf of the squared length (fixed-point units) of edge i, opposite vertex i
     int pad[2];
 };
 static_assert(sizeof(TriSetup) == 96, "setup record is 96 bytes");
@@ -169,7 +169,7 @@ __device__ __forceinline__ TriSetup dr_setup(const float4 *pc, int v0, int v1, i
     s.box1 = 1;
     s.hbox0 = s.hbox1 = 1;
     s.zlb = 0;
-    s.il[0] = s.il[1] = s.il[2] = 0.0f;
+    s.elen[0] = s.elen[1] = s.elen[2] = 0.0f;
     s.pad[0] = s.pad[1] = 0;
     const int vid[3] = {v0, v1, v2};
     float4 p[3];
@@ -225,8 +225,8 @@ __device__ __forceinline__ TriSetup dr_setup(const float4 *pc, int v0, int v1, i
 #pragma unroll
         for (int i = 0; i < 3; i++) {
             int a = (i + 1) % 3, c = (i + 2) % 3;
-            float ex = (float)(s.X[c] - s.X[a]), ey = (float)(s.Y[c] - s.Y[a]);
-            s.il[i] = 1.0f / sqrtf(ex * ex + ey * ey);
+            double ex = (double)(s.X[c] - s.X[a]), ey = (double)(s.Y[c] - s.Y[a]);
+            s.elen[i] = sqrtf((float)(ex * ex + ey * ey));
         }
     }
     x0 = max(x0, 0); y0 = max(y0, 0);

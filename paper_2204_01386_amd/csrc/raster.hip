@@ -20,6 +20,7 @@
 #include "dressi_internal.h"
 
 #include <algorithm>
+#include <type_traits>
 #include <cfloat>
 
 // ---------------------------------------------------------------------------
@@ -296,11 +297,69 @@ __device__ __forceinline__ float wave_max(float v) {
 __device__ __forceinline__ int lo16(int v) { return (int)(short)(v & 0xffff); }
 __device__ __forceinline__ int hi16(int v) { return v >> 16; }
 
+// Smallest segment distance (fixed-point units) from the pixel centre to the
+// triangle: the same value as the minimum of the three segment distances in
+// their usual form, computed without branches.  Every integer product and sum
+// is exact in double; el[i] is sqrtf of edge i's squared length.
+template <typename TE>
+__device__ __forceinline__ float rl_segmin(const TriSetup &s, const TE *E, const float *el, int px, int py) {
+    double qx[3], qy[3], dv[3];
+#pragma unroll
+    for (int v = 0; v < 3; v++) {
+        qx[v] = (double)(px - s.X[v]);
+        qy[v] = (double)(py - s.Y[v]);
+        dv[v] = qx[v] * qx[v] + qy[v] * qy[v];
+    }
+    float d[3];
+#pragma unroll
+    for (int i = 0; i < 3; i++) {
+        const int a = (i + 1) % 3, b = (i + 2) % 3;
+        const double ex = (double)(s.X[b] - s.X[a]), ey = (double)(s.Y[b] - s.Y[a]);
+        const double dot = qx[a] * ex + qy[a] * ey;
+        const double len2 = ex * ex + ey * ey;
+        const bool va = dot <= 0.0, vb = dot >= len2;
+        const float sv = sqrtf((float)(va ? dv[a] : dv[b]));        // nearest point: a vertex
+        const float si = (float)(E[i] < 0 ? -E[i] : E[i]) / el[i];  // nearest point inside the edge
+        d[i] = (va || vb) ? sv : si;
+    }
+    float best = d[0];
+    if (d[1] < best) best = d[1];
+    if (d[2] < best) best = d[2];
+    return best;
+}
+
+// The same value when every coordinate difference over the tile is below
+// 2^15 in magnitude: products and sums of two products then stay below 2^31
+// and 24-bit integer multiplies give them exactly.  q[v] = (px - X_v, py - Y_v).
+__device__ __forceinline__ float rl_segmin_i(const int *qx, const int *qy, const int *ex, const int *ey,
+                                             const int *len2, const int *E, const float *el) {
+    int dv[3];
+#pragma unroll
+    for (int v = 0; v < 3; v++) dv[v] = __mul24(qx[v], qx[v]) + __mul24(qy[v], qy[v]);
+    float d[3];
+#pragma unroll
+    for (int i = 0; i < 3; i++) {
+        const int a = (i + 1) % 3, b = (i + 2) % 3;
+        const int dot = __mul24(qx[a], ex[i]) + __mul24(qy[a], ey[i]);
+        const bool va = dot <= 0, vb = dot >= len2[i];
+        const float sv = sqrtf((float)(va ? dv[a] : dv[b]));
+        const float si = (float)(E[i] < 0 ? -E[i] : E[i]) / el[i];
+        d[i] = (va || vb) ? sv : si;
+    }
+    float best = d[0];
+    if (d[1] < best) best = d[1];
+    if (d[2] < best) best = d[2];
+    return best;
+}
+
 // Merges the candidate fragment of triangle t at this lane's pixel.  MAYHARD
 // is false when no pixel centre of the wavefront can be inside the triangle.
 template <int K, bool MAYHARD, typename TE>
-__device__ __forceinline__ void rl_merge(const TriSetup &s, const TE *E, const float *il, int t, int px,
-                                         int py, float dscale, float r, float reach, float *key, int *id) {
+__device__ __forceinline__ void rl_merge(const TriSetup &s, const TE *E, const float *el, int t, int px,
+                                         int py, float dscale, float r, float reach, float *key, int *id,
+                                         const int *qx = nullptr, const int *qy = nullptr,
+                                         const int *ex = nullptr, const int *ey = nullptr,
+                                         const int *len2 = nullptr) {
     bool in = MAYHARD;
     if (MAYHARD) {
 #pragma unroll
@@ -315,21 +374,23 @@ __device__ __forceinline__ void rl_merge(const TriSetup &s, const TE *E, const f
         if (!(z > 0.0f && z < 1.0f)) return;
         kf = 0.5f * z;
     } else {
-        // The distance to the triangle is at least the distance to the line
-        // of any edge the pixel lies outside of.  A soft fragment enters the
-        // list only if its key 0.5 + dn/2 is at most the list's last key, so
-        // it needs dn <= 2 (last - 0.5) (+ one rounding of the key) and
-        // dn <= r.  The bound is compared with a relative margin far above the
-        // float rounding of either side, so every fragment dropped here would
-        // also fail the exact tests below.
-        float ld = 0.0f;
-        if (E[0] < 0) ld = fmaxf(ld, (float)(-E[0]) * il[0]);
-        if (E[1] < 0) ld = fmaxf(ld, (float)(-E[1]) * il[1]);
-        if (E[2] < 0) ld = fmaxf(ld, (float)(-E[2]) * il[2]);
+        // The distance to the triangle is at least the distance -E_i / |e_i|
+        // to the line of any edge the pixel lies outside of.  A soft fragment
+        // enters the list only if its key 0.5 + dn/2 is at most the list's
+        // last key, so it needs dn <= 2 (last - 0.5) (+ one rounding of the
+        // key) and dn <= r.  The bound is compared with a relative margin far
+        // above the float rounding of either side, so every fragment dropped
+        // here would also fail the exact tests below.
         const float lim = fminf(reach, (2.0f * (key[K - 1] - 0.5f) + 2.4e-7f) * dscale * 1.001f);
-        if (ld > lim) return;
-        int ne;
-        float dn = dr_distnorm(s.X, s.Y, px, py, E, dscale, ne);
+        if ((E[0] < 0 && (float)(-E[0]) > lim * el[0]) || (E[1] < 0 && (float)(-E[1]) > lim * el[1]) ||
+            (E[2] < 0 && (float)(-E[2]) > lim * el[2]))
+            return;
+        float best;
+        if constexpr (std::is_integral<TE>::value)
+            best = rl_segmin_i(qx, qy, ex, ey, len2, E, el);
+        else
+            best = rl_segmin(s, E, el, px, py);
+        float dn = best / dscale;
         if (!(dn <= r)) return;
         float h = 0.5f * dn;
         kf = h + 0.5f;
@@ -362,7 +423,7 @@ __device__ __forceinline__ void rl_merge(const TriSetup &s, const TE *E, const f
 }
 
 template <int K>
-__global__ void __launch_bounds__(DRESSI_TILE_PIX)
+__global__ void __launch_bounds__(DRESSI_TILE_PIX) __attribute__((amdgpu_waves_per_eu(5)))
     k_raster_list(const TriSetup *__restrict__ setup, int32_t *__restrict__ counts,
                   const int32_t *__restrict__ bins, int cap, int T, int H, int W, int ntx, int nt,
                   float r, int32_t *__restrict__ tri_id, float2 *__restrict__ bary,
@@ -373,10 +434,12 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX)
     __shared__ int2 sbox[RL_BATCH];     // soft box
     __shared__ int2 shb[RL_BATCH];      // pixels with centres in the vertex box
     __shared__ int szlb[RL_BATCH];      // lower bound of the hard keys (float bits)
-    __shared__ float4 se[3][RL_BATCH];  // per edge: E at the tile's first pixel, 256 ex, 256 ey, 1/|e|
+    __shared__ float4 sel[RL_BATCH];    // sqrtf of the squared edge lengths
     __shared__ int4 sxy0[RL_BATCH];     // X0 X1 X2 Y0
     __shared__ int2 sxy1[RL_BATCH];     // Y1 Y2
     __shared__ float4 sz[RL_BATCH];     // zn0 zn1 zn2 Af
+    __shared__ int4 sed[RL_BATCH];      // edge vectors (ex | ey << 16) of the 32-bit path
+    __shared__ int4 slen[RL_BATCH];     // their squared lengths
     const int bt = blockIdx.x;
     const int b = bt / nt, tile = bt - b * nt;
     const int tx = tile % ntx, ty = tile / ntx;
@@ -387,7 +450,6 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX)
     const int y = ty * DRESSI_TILE + ly;
     const int px = DRESSI_SUBPIX * x + DRESSI_SUBPIX / 2;
     const int py = DRESSI_SUBPIX * y + DRESSI_SUBPIX / 2;
-    const float flx = (float)lx, fly = (float)ly;
     const float dscale = (float)W * 256.0f;
     const float reach = r * dscale * 1.001f;   // conservative, in fixed-point units
     const TriSetup *__restrict__ sv = setup + (int64_t)b * T;
@@ -419,21 +481,26 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX)
                 if (p < n) {
                     const int t = bin[c0 + p];
                     const TriSetup s = sv[t];
-                    bool fast = true;
+                    // 32-bit integer path: every pixel-to-vertex difference over the
+                    // tile and every edge vector below 2^15 in magnitude
+                    const int lim15 = 1 << 15, span = DRESSI_SUBPIX * (DRESSI_TILE - 1);
+                    bool small = true;
+                    int exy[3], l2[3];
 #pragma unroll
                     for (int i = 0; i < 3; i++) {
+                        small = small && abs(px0 - s.X[i]) < lim15 && abs(px0 + span - s.X[i]) < lim15 &&
+                                abs(py0 - s.Y[i]) < lim15 && abs(py0 + span - s.Y[i]) < lim15;
                         const int a = (i + 1) % 3, c = (i + 2) % 3;
                         const int ex = s.X[c] - s.X[a], ey = s.Y[c] - s.Y[a];
-                        const double e0 = (double)ex * (double)(py0 - s.Y[a]) - (double)ey * (double)(px0 - s.X[a]);
-                        // E is affine: its extremes over the tile are at the corner pixels
-                        const double dx = (double)(DRESSI_SUBPIX * (DRESSI_TILE - 1)) * (double)ey;
-                        const double dy = (double)(DRESSI_SUBPIX * (DRESSI_TILE - 1)) * (double)ex;
-                        const double m = fmax(fmax(fabs(e0), fabs(e0 - dx)), fmax(fabs(e0 + dy), fabs(e0 + dy - dx)));
-                        fast = fast && m < 16777216.0;
-                        se[i][p] = make_float4((float)e0, 256.0f * (float)ex, 256.0f * (float)ey, s.il[i]);
+                        small = small && abs(ex) < lim15 && abs(ey) < lim15;
+                        exy[i] = (ex & 0xffff) | (ey << 16);
+                        l2[i] = small ? ex * ex + ey * ey : 0;
                     }
+                    sed[p] = make_int4(exy[0], exy[1], exy[2], 0);
+                    sel[p] = make_float4(s.elen[0], s.elen[1], s.elen[2], 0.0f);
+                    slen[p] = make_int4(l2[0], l2[1], l2[2], 0);
                     sid[p] = t;
-                    sflag[p] = (s.meta & 0xffff) | (fast ? 0x10000 : 0);
+                    sflag[p] = (s.meta & 0xffff) | (small ? 0x10000 : 0);
                     sbox[p] = make_int2(s.box0, s.box1);
                     shb[p] = make_int2(s.hbox0, s.hbox1);
                     szlb[p] = s.zlb;
@@ -465,7 +532,7 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX)
                     todo &= todo - 1ull;
                     const int fl = sflag[j];
                     const int t = sid[j];
-                    const float4 e0 = se[0][j], e1 = se[1][j], e2 = se[2][j];
+                    const float4 e4 = sel[j];
                     const int4 q0 = sxy0[j];
                     const int2 q1 = sxy1[j];
                     const float4 z4 = sz[j];
@@ -475,21 +542,35 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX)
                     s.zn[0] = z4.x; s.zn[1] = z4.y; s.zn[2] = z4.z;
                     s.Af = z4.w;
                     s.meta = fl & 0xffff;
-                    const float il[3] = {e0.w, e1.w, e2.w};
+                    const float el[3] = {e4.x, e4.y, e4.z};
                     if (fl >> 16) {
-                        // exact: every partial result is an integer below 2^24
-                        float E[3];
-                        E[0] = fmaf(e0.y, fly, fmaf(-e0.z, flx, e0.x));
-                        E[1] = fmaf(e1.y, fly, fmaf(-e1.z, flx, e1.x));
-                        E[2] = fmaf(e2.y, fly, fmaf(-e2.z, flx, e2.x));
-                        if (walk == 0) rl_merge<K, true>(s, E, il, t, px, py, dscale, r, reach, key, id);
-                        else rl_merge<K, false>(s, E, il, t, px, py, dscale, r, reach, key, id);
+                        // exact in 32-bit integers (see the staging test)
+                        const int4 ed = sed[j];
+                        const int4 ln = slen[j];
+                        const int ex[3] = {lo16(ed.x), lo16(ed.y), lo16(ed.z)};
+                        const int ey[3] = {hi16(ed.x), hi16(ed.y), hi16(ed.z)};
+                        const int len2[3] = {ln.x, ln.y, ln.z};
+                        int qx[3], qy[3], E[3];
+#pragma unroll
+                        for (int v = 0; v < 3; v++) {
+                            qx[v] = px - s.X[v];
+                            qy[v] = py - s.Y[v];
+                        }
+#pragma unroll
+                        for (int i = 0; i < 3; i++) {
+                            const int a = (i + 1) % 3;
+                            E[i] = __mul24(ex[i], qy[a]) - __mul24(ey[i], qx[a]);
+                        }
+                        if (walk == 0)
+                            rl_merge<K, true>(s, E, el, t, px, py, dscale, r, reach, key, id, qx, qy, ex, ey, len2);
+                        else
+                            rl_merge<K, false>(s, E, el, t, px, py, dscale, r, reach, key, id, qx, qy, ex, ey, len2);
                     } else {
                         double E[3];
 #pragma unroll
                         for (int i = 0; i < 3; i++) E[i] = dr_edge(s.X, s.Y, i, px, py);
-                        if (walk == 0) rl_merge<K, true>(s, E, il, t, px, py, dscale, r, reach, key, id);
-                        else rl_merge<K, false>(s, E, il, t, px, py, dscale, r, reach, key, id);
+                        if (walk == 0) rl_merge<K, true>(s, E, el, t, px, py, dscale, r, reach, key, id);
+                        else rl_merge<K, false>(s, E, el, t, px, py, dscale, r, reach, key, id);
                     }
                 }
                 // keys only decrease: refresh the strip's bounds
