@@ -104,7 +104,8 @@ class Shapes:
         self.mode = st.mode
         self.ex = st.extra is not None
         self.Vuv = 0 if st.uv is None else st.uv.shape[0]
-        self.Ct = st.Ct
+        # channels the method samples (a packed texture's zero padding channel is overhead)
+        self.Ct = st.Ct - (1 if st.Ct and st.scene.nmap is not None else 0)
         self.cells = 0 if st.tex is None else st.tex.shape[0] * st.tex.shape[1]
         self.env = st.env is not None
         self.ecells = 0 if st.env is None else st.env.shape[0] * st.env.shape[1] * st.env.shape[2]
@@ -294,12 +295,21 @@ def measure(scene, steps, warmup, prof_steps, plain_steps_min=10):
     if n < 0:
         raise SystemExit(f"kernel profiler failed ({n})")
     per = {}
+    per_launch = {}   # (name, occurrence within the step) -> total ms
     for i in range(n):
         k = names[i].decode()
         tot, cnt = per.get(k, (0.0, 0))
         per[k] = (tot + ms[i], cnt + 1)
+    launches = n // prof_steps if prof_steps else 0
+    for i in range(n):
+        k = names[i].decode()
+        j = i % launches if launches else i
+        per_launch.setdefault((j, k), 0.0)
+        per_launch[(j, k)] += ms[i]
     res["table"] = sorted(((k, tot / prof_steps, tot / cnt, cnt // prof_steps)
                            for k, (tot, cnt) in per.items()), key=lambda x: -x[1])
+    res["launches"] = sorted(((f"{k}@{j}", tot / prof_steps) for (j, k), tot in per_launch.items()),
+                             key=lambda x: -x[1])
     res["cov"] = int((st.tri_id >= 0).sum().item())
     return res
 
@@ -337,6 +347,7 @@ def main():
     kernel_rows = [{"kernel": k, "ms_per_step": round(a, 5), "ms_per_launch": round(b, 5),
                     "launches_per_step": c, "alg_bytes": kernel_bytes(k, z)} for k, a, b, c in table]
     ms_plain = m["plain_ms_per_step"]
+    launch_rows = [{"launch": k, "ms": round(a, 5)} for k, a in m["launches"][:16]]
     del m
 
     # ---- the 16-view batched configuration beside its per-view form -------
@@ -356,7 +367,8 @@ def main():
                  "step_alg_bytes": b3,
                  "step_hbm_frac": round(b3 / (m3["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                  "kernels": [{"kernel": k, "ms_per_step": round(a, 5), "launches_per_step": c}
-                             for k, a, b, c in m3["table"][:12]]}
+                             for k, a, b, c in m3["table"][:12]],
+                 "launches": [{"launch": k, "ms": round(a, 5)} for k, a in m3["launches"][:16]]}
         del m3
 
     # ---- CPU baseline: the oracle's step on the same workload --------------
@@ -411,6 +423,7 @@ def main():
         "cpu_baseline": cpu,
         "multiview": multi,
         "kernels": kernel_rows,
+        "launches": launch_rows,
     }
     print(json.dumps(res))
 

@@ -60,7 +60,7 @@ typedef struct dressi_ctx dressi_ctx;
 
 typedef struct {
     int kind;           /* DRESSI_TEX_2D or DRESSI_TEX_CUBE (then Ht == Wt == S) */
-    int Ht, Wt, Ct;     /* texels per column, per row, channels (1..16)          */
+    int Ht, Wt, Ct;     /* texels per column, per row (1..32767), channels (1..16) */
     int wrap_u, wrap_v; /* 2D only; repeat needs Wt (Ht) >= 3                     */
 } dressi_tex_desc;
 

@@ -57,6 +57,18 @@ bool dr_prof_slot(const char *name, hipEvent_t *start, hipEvent_t *stop);
                                __VA_ARGS__);                                    \
     } while (0)
 
+// Inverse-UV gather: slices whose cell halos are loaded together, and the
+// split of the slices over the grid for small textures (with its scratch of
+// partial sums).
+#define DRESSI_IV_SG 4
+static inline int dressi_invuv_nsplit(int64_t cells, int S) {
+    return (cells < (1 << 19) && S > DRESSI_IV_SG) ? (S + DRESSI_IV_SG - 1) / DRESSI_IV_SG : 1;
+}
+static inline size_t dressi_invuv_part_bytes(int64_t cells, int Ct, int S) {
+    int ns = dressi_invuv_nsplit(cells, S);
+    return ns > 1 ? sizeof(float) * (size_t)cells * Ct * ns : 0;
+}
+
 // Bump allocator over the arena: carve(n) returns 256-byte aligned offsets.
 struct Carver {
     size_t off = 0;

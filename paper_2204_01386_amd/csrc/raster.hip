@@ -1202,6 +1202,7 @@ extern "C" size_t dressi_scratch_bytes(int B, int V, int T, int H, int W, int K,
     {
         Carver c;
         c.take(sizeof(int32_t) * (size_t)tex_cells * (tex_slices > 0 ? tex_slices : 1));
+        c.take(dressi_invuv_part_bytes(tex_cells, 16, tex_slices));
         upd(c.off);
     }
     {

@@ -95,51 +95,87 @@ __device__ __forceinline__ Taps make_taps(const dressi_tex_desc &td, const float
     return t;
 }
 
-__global__ void k_tex_fwd(const float *__restrict__ tex, dressi_tex_desc td,
-                          const float *__restrict__ coord, const int32_t *__restrict__ tri_id,
-                          int64_t n, float *__restrict__ out) {
+// CT channels per texel or pixel (CT = 0: Ct at run time, at most 16).
+// Multiples of 4 are moved as float4 (16-byte aligned rows).
+template <int CT>
+__device__ __forceinline__ void ldv(const float *__restrict__ p, float *v, int Ct) {
+    if constexpr (CT > 0 && CT % 4 == 0) {
+#pragma unroll
+        for (int q = 0; q < CT / 4; q++) {
+            const float4 a = reinterpret_cast<const float4 *>(p)[q];
+            v[4 * q] = a.x; v[4 * q + 1] = a.y; v[4 * q + 2] = a.z; v[4 * q + 3] = a.w;
+        }
+    } else if constexpr (CT > 0) {
+#pragma unroll
+        for (int c = 0; c < CT; c++) v[c] = p[c];
+    } else {
+#pragma unroll
+        for (int c = 0; c < 16; c++)
+            if (c < Ct) v[c] = p[c];
+    }
+}
+
+template <int CT>
+__device__ __forceinline__ void stv(float *__restrict__ p, const float *v, int Ct) {
+    if constexpr (CT > 0 && CT % 4 == 0) {
+#pragma unroll
+        for (int q = 0; q < CT / 4; q++)
+            reinterpret_cast<float4 *>(p)[q] = make_float4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
+    } else if constexpr (CT > 0) {
+#pragma unroll
+        for (int c = 0; c < CT; c++) p[c] = v[c];
+    } else {
+#pragma unroll
+        for (int c = 0; c < 16; c++)
+            if (c < Ct) p[c] = v[c];
+    }
+}
+
+#define TEX_NC(CT) ((CT) > 0 ? (CT) : 16)
+
+template <int CT>
+__global__ void __launch_bounds__(256)
+    k_tex_fwd(const float *__restrict__ tex, dressi_tex_desc td, const float *__restrict__ coord,
+              const int32_t *__restrict__ tri_id, int64_t n, float *__restrict__ out) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const int Ct = td.Ct;
+    const int Ct = CT > 0 ? CT : td.Ct;
     const int cd = td.kind == DRESSI_TEX_CUBE ? 3 : 2;
     float *y = out + i * Ct;
+    float r[TEX_NC(CT)];
     Taps t;
     t.ok = 0;
     if (!tri_id || tri_id[i] >= 0) t = make_taps(td, coord + i * cd);
     if (!t.ok) {
-        for (int c = 0; c < Ct; c++) y[c] = 0.0f;
+#pragma unroll
+        for (int c = 0; c < TEX_NC(CT); c++) r[c] = 0.0f;
+        stv<CT>(y, r, Ct);
         return;
     }
     const int64_t face = (int64_t)t.face * td.Ht * td.Wt;
-    const float *p00 = tex + (face + (int64_t)t.y0 * td.Wt + t.x0) * Ct;
-    const float *p01 = tex + (face + (int64_t)t.y0 * td.Wt + t.x1) * Ct;
-    const float *p10 = tex + (face + (int64_t)t.y1 * td.Wt + t.x0) * Ct;
-    const float *p11 = tex + (face + (int64_t)t.y1 * td.Wt + t.x1) * Ct;
-    float w00 = (1.0f - t.fy) * (1.0f - t.fx), w01 = (1.0f - t.fy) * t.fx;
-    float w10 = t.fy * (1.0f - t.fx), w11 = t.fy * t.fx;
-    if (Ct == 4) {
-        float4 a = *reinterpret_cast<const float4 *>(p00), b = *reinterpret_cast<const float4 *>(p01);
-        float4 c = *reinterpret_cast<const float4 *>(p10), d = *reinterpret_cast<const float4 *>(p11);
-        float4 r;
-        r.x = w00 * a.x + w01 * b.x + w10 * c.x + w11 * d.x;
-        r.y = w00 * a.y + w01 * b.y + w10 * c.y + w11 * d.y;
-        r.z = w00 * a.z + w01 * b.z + w10 * c.z + w11 * d.z;
-        r.w = w00 * a.w + w01 * b.w + w10 * c.w + w11 * d.w;
-        *reinterpret_cast<float4 *>(y) = r;
-        return;
-    }
-    for (int c = 0; c < Ct; c++) y[c] = w00 * p00[c] + w01 * p01[c] + w10 * p10[c] + w11 * p11[c];
+    float a[TEX_NC(CT)], b[TEX_NC(CT)], c4[TEX_NC(CT)], d[TEX_NC(CT)];
+    ldv<CT>(tex + (face + (int64_t)t.y0 * td.Wt + t.x0) * Ct, a, Ct);
+    ldv<CT>(tex + (face + (int64_t)t.y0 * td.Wt + t.x1) * Ct, b, Ct);
+    ldv<CT>(tex + (face + (int64_t)t.y1 * td.Wt + t.x0) * Ct, c4, Ct);
+    ldv<CT>(tex + (face + (int64_t)t.y1 * td.Wt + t.x1) * Ct, d, Ct);
+    const float w00 = (1.0f - t.fy) * (1.0f - t.fx), w01 = (1.0f - t.fy) * t.fx;
+    const float w10 = t.fy * (1.0f - t.fx), w11 = t.fy * t.fx;
+#pragma unroll
+    for (int c = 0; c < TEX_NC(CT); c++) r[c] = w00 * a[c] + w01 * b[c] + w10 * c4[c] + w11 * d[c];
+    stv<CT>(y, r, Ct);
 }
 
 // Per pixel: d out / d coord and, when `inv` is given, the inverse-UV record
 // (the pixel index written into its cell with atomicMax).
-__global__ void k_tex_bwd_pixel(const float *__restrict__ tex, dressi_tex_desc td,
+template <int CT>
+__global__ void __launch_bounds__(256)
+    k_tex_bwd_pixel(const float *__restrict__ tex, dressi_tex_desc td,
                                 const float *__restrict__ coord, const int32_t *__restrict__ tri_id,
                                 int64_t npix, int S, const float *__restrict__ grad_out,
                                 float *__restrict__ grad_coord, int32_t *__restrict__ inv) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= (int64_t)S * npix) return;
-    const int Ct = td.Ct;
+    const int Ct = CT > 0 ? CT : td.Ct;
     const bool cube = td.kind == DRESSI_TEX_CUBE;
     const int cd = cube ? 3 : 2;
     const float *q = coord + i * cd;
@@ -170,13 +206,16 @@ __global__ void k_tex_bwd_pixel(const float *__restrict__ tex, dressi_tex_desc t
         return;
     }
     const int64_t face = (int64_t)t.face * td.Ht * td.Wt;
-    const float *p00 = tex + (face + (int64_t)t.y0 * td.Wt + t.x0) * Ct;
-    const float *p01 = tex + (face + (int64_t)t.y0 * td.Wt + t.x1) * Ct;
-    const float *p10 = tex + (face + (int64_t)t.y1 * td.Wt + t.x0) * Ct;
-    const float *p11 = tex + (face + (int64_t)t.y1 * td.Wt + t.x1) * Ct;
-    const float *g = grad_out + i * Ct;
+    float p00[TEX_NC(CT)], p01[TEX_NC(CT)], p10[TEX_NC(CT)], p11[TEX_NC(CT)], g[TEX_NC(CT)];
+    ldv<CT>(tex + (face + (int64_t)t.y0 * td.Wt + t.x0) * Ct, p00, Ct);
+    ldv<CT>(tex + (face + (int64_t)t.y0 * td.Wt + t.x1) * Ct, p01, Ct);
+    ldv<CT>(tex + (face + (int64_t)t.y1 * td.Wt + t.x0) * Ct, p10, Ct);
+    ldv<CT>(tex + (face + (int64_t)t.y1 * td.Wt + t.x1) * Ct, p11, Ct);
+    ldv<CT>(grad_out + i * Ct, g, Ct);
     float du = 0.0f, dv = 0.0f;
-    for (int c = 0; c < Ct; c++) {
+#pragma unroll
+    for (int c = 0; c < TEX_NC(CT); c++) {
+        if (CT == 0 && c >= Ct) break;
         du += g[c] * ((1.0f - t.fy) * (p01[c] - p00[c]) + t.fy * (p11[c] - p10[c]));
         dv += g[c] * ((1.0f - t.fx) * (p10[c] - p00[c]) + t.fx * (p11[c] - p01[c]));
     }
@@ -215,76 +254,140 @@ __global__ void k_tex_bwd_pixel(const float *__restrict__ tex, dressi_tex_desc t
 // weight on the texel.
 #define IV_T 16
 #define IV_H (IV_T + 2)
+// Per texel: the sum over slices [s0, s1), in ascending order, of the distinct
+// in-range cells of its 3x3 block, row-major, of the winner pixel's bilinear
+// weight on this texel times its gradient.  A 16x16 block of texels loads the
+// 18x18 halo of cells of DRESSI_IV_SG slices at once (all loads in flight), skips the
+// group when every cell is empty, then gathers.  With nsplit > 1 the slice
+// range is split over grid.z and each part writes its own partial sum.
 template <int CT>
 __global__ void __launch_bounds__(IV_T * IV_T)
-    k_invuv_gather(dressi_tex_desc td, const float *__restrict__ coord, int64_t npix, int S,
+    k_invuv_gather(dressi_tex_desc td, const float *__restrict__ coord, int64_t npix, int S, int nsplit,
                    const int32_t *__restrict__ inv, const float *__restrict__ grad_out,
-                   float *__restrict__ grad_tex) {
-    __shared__ int cells[IV_H * IV_H];
+                   float *__restrict__ out) {
+    // per halo cell of each slice of the group: the winner pixel (-1: none or
+    // another cube face), its four tap coordinates and bilinear fractions
+    __shared__ int cpix[DRESSI_IV_SG][IV_H * IV_H];
+    __shared__ int2 ctap[DRESSI_IV_SG][IV_H * IV_H];   // x0 | x1 << 16, y0 | y1 << 16
+    __shared__ float2 cfr[DRESSI_IV_SG][IV_H * IV_H];  // fx, fy
     const int Ht = td.Ht, Wt = td.Wt, Ct = CT > 0 ? CT : td.Ct;
     const bool cube = td.kind == DRESSI_TEX_CUBE;
     const int F = cube ? 6 : 1;
     const int wu = cube ? DRESSI_WRAP_CLAMP : td.wrap_u;
     const int wv = cube ? DRESSI_WRAP_CLAMP : td.wrap_v;
     const int cd = cube ? 3 : 2;
-    const int f = blockIdx.z;
+    const int f = blockIdx.z / nsplit, part = blockIdx.z - f * nsplit;
+    const int per = (S + nsplit - 1) / nsplit;
+    const int s0 = part * per, s1 = min(S, s0 + per);
     const int bx0 = blockIdx.x * IV_T, by0 = blockIdx.y * IV_T;
     const int lx = threadIdx.x % IV_T, ly = threadIdx.x / IV_T;
     const int tx = bx0 + lx, ty = by0 + ly;
     const bool mine = tx < Wt && ty < Ht;
-    const int64_t cells_all = (int64_t)F * Ht * Wt;
-    float acc[16];
+    const int64_t face_cells = (int64_t)Ht * Wt;
+    const int64_t cells_all = (int64_t)F * face_cells;
+    // this thread's halo entries (row-major over the 18x18 halo) and their cell offsets
+    int hoff[2];
 #pragma unroll
-    for (int c = 0; c < 16; c++) acc[c] = 0.0f;
-    for (int s = 0; s < S; s++) {
-        const int32_t *iv = inv + (int64_t)s * cells_all + (int64_t)f * Ht * Wt;
-        int found = 0;
-        for (int h = threadIdx.x; h < IV_H * IV_H; h += IV_T * IV_T) {
+    for (int k = 0; k < 2; k++) {
+        const int h = threadIdx.x + k * IV_T * IV_T;
+        hoff[k] = -1;
+        if (h < IV_H * IV_H) {
             int cy = by0 - 1 + h / IV_H, cx = bx0 - 1 + h % IV_H;
             bool ok = true;
             if (wv == DRESSI_WRAP_REPEAT) cy = ((cy % Ht) + Ht) % Ht;
             else ok = cy >= 0 && cy < Ht;
             if (wu == DRESSI_WRAP_REPEAT) cx = ((cx % Wt) + Wt) % Wt;
             else ok = ok && cx >= 0 && cx < Wt;
-            int v = ok ? iv[(int64_t)cy * Wt + cx] : -1;
-            cells[h] = v;
-            found |= v >= 0;
+            if (ok) hoff[k] = cy * Wt + cx;
+        }
+    }
+    float acc[TEX_NC(CT)];
+#pragma unroll
+    for (int c = 0; c < TEX_NC(CT); c++) acc[c] = 0.0f;
+    for (int g0 = s0; g0 < s1; g0 += DRESSI_IV_SG) {
+        const int ng = min(DRESSI_IV_SG, s1 - g0);
+        // winners of the group's halo cells (all loads in flight)
+        int wpix[DRESSI_IV_SG][2];
+#pragma unroll
+        for (int q = 0; q < DRESSI_IV_SG; q++) {
+            const int32_t *iv = inv + (int64_t)(g0 + q) * cells_all + (int64_t)f * face_cells;
+#pragma unroll
+            for (int k = 0; k < 2; k++) wpix[q][k] = (q < ng && hoff[k] >= 0) ? iv[hoff[k]] : -1;
+        }
+        int found = 0;
+        // each winner's taps, computed once for the up to 9 texels that visit it
+#pragma unroll
+        for (int q = 0; q < DRESSI_IV_SG; q++) {
+#pragma unroll
+            for (int k = 0; k < 2; k++) {
+                const int h = threadIdx.x + k * IV_T * IV_T;
+                if (h >= IV_H * IV_H) continue;
+                int i = wpix[q][k];
+                int2 tp = make_int2(0, 0);
+                float2 fr = make_float2(0.0f, 0.0f);
+                if (i >= 0) {
+                    const Taps t = make_taps(td, coord + ((int64_t)(g0 + q) * npix + i) * cd);
+                    if (!t.ok || t.face != f) {
+                        i = -1;
+                    } else {
+                        tp = make_int2(t.x0 | (t.x1 << 16), t.y0 | (t.y1 << 16));
+                        fr = make_float2(t.fx, t.fy);
+                    }
+                }
+                cpix[q][h] = i;
+                ctap[q][h] = tp;
+                cfr[q][h] = fr;
+                found |= i >= 0;
+            }
         }
         if (!__syncthreads_or(found)) continue;
         if (mine) {
+            for (int q = 0; q < ng; q++) {
+                const int s = g0 + q;
 #pragma unroll
-            for (int dy = 0; dy < 3; dy++) {
+                for (int dy = 0; dy < 3; dy++) {
 #pragma unroll
-                for (int dx = 0; dx < 3; dx++) {
-                    int i = cells[(ly + dy) * IV_H + lx + dx];
-                    if (i < 0) continue;
-                    int64_t o = (int64_t)s * npix + i;
-                    Taps t = make_taps(td, coord + o * cd);
-                    if (!t.ok || t.face != f) continue;
-                    float w = 0.0f;
-                    if (t.y0 == ty && t.x0 == tx) w += (1.0f - t.fy) * (1.0f - t.fx);
-                    if (t.y0 == ty && t.x1 == tx) w += (1.0f - t.fy) * t.fx;
-                    if (t.y1 == ty && t.x0 == tx) w += t.fy * (1.0f - t.fx);
-                    if (t.y1 == ty && t.x1 == tx) w += t.fy * t.fx;
-                    if (w == 0.0f) continue;
-                    const float *g = grad_out + o * Ct;
+                    for (int dx = 0; dx < 3; dx++) {
+                        const int h = (ly + dy) * IV_H + lx + dx;
+                        const int i = cpix[q][h];
+                        if (i < 0) continue;
+                        const int2 tp = ctap[q][h];
+                        const float2 fr = cfr[q][h];
+                        const int x0 = tp.x & 0xffff, x1 = tp.x >> 16, y0 = tp.y & 0xffff, y1 = tp.y >> 16;
+                        float w = 0.0f;
+                        if (y0 == ty && x0 == tx) w += (1.0f - fr.y) * (1.0f - fr.x);
+                        if (y0 == ty && x1 == tx) w += (1.0f - fr.y) * fr.x;
+                        if (y1 == ty && x0 == tx) w += fr.y * (1.0f - fr.x);
+                        if (y1 == ty && x1 == tx) w += fr.y * fr.x;
+                        if (w == 0.0f) continue;
+                        float g[TEX_NC(CT)];
+                        ldv<CT>(grad_out + ((int64_t)s * npix + i) * Ct, g, Ct);
 #pragma unroll
-                    for (int c = 0; c < 16; c++)
-                        if (c < Ct) acc[c] += w * g[c];
+                        for (int c = 0; c < TEX_NC(CT); c++)
+                            if (CT > 0 || c < Ct) acc[c] += w * g[c];
+                    }
                 }
             }
         }
         __syncthreads();
     }
     if (!mine) return;
-    float *gt = grad_tex + ((int64_t)f * Ht * Wt + (int64_t)ty * Wt + tx) * Ct;
-    if (Ct == 4) {
-        *reinterpret_cast<float4 *>(gt) = make_float4(acc[0], acc[1], acc[2], acc[3]);
-        return;
-    }
-#pragma unroll
-    for (int c = 0; c < 16; c++)
-        if (c < Ct) gt[c] = acc[c];
+    float *gt = out + ((int64_t)part * cells_all + (int64_t)f * face_cells + (int64_t)ty * Wt + tx) * Ct;
+    stv<CT>(gt, acc, Ct);
+}
+
+// Sums the per-part partial texture gradients in part order.
+__global__ void k_invuv_reduce(const float *__restrict__ part, int nsplit, int64_t n, float *__restrict__ out) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float a = part[i];
+    for (int k = 1; k < nsplit; k++) a += part[(int64_t)k * n + i];
+    out[i] = a;
+}
+
+// float4 rows need 16-byte aligned bases
+static bool aligned16(const void *a, const void *b) {
+    return (((uintptr_t)a | (uintptr_t)b) & 15u) == 0;
 }
 
 static int check_tex(dressi_ctx *ctx, const void *tex, const dressi_tex_desc *td, const void *coord,
@@ -293,8 +396,8 @@ static int check_tex(dressi_ctx *ctx, const void *tex, const dressi_tex_desc *td
     if (!td) return dressi_fail(ctx, DRESSI_EINVAL, "texture: null descriptor");
     if (td->kind != DRESSI_TEX_2D && td->kind != DRESSI_TEX_CUBE)
         return dressi_fail(ctx, DRESSI_EINVAL, "texture: bad kind");
-    if (td->Ht < 1 || td->Wt < 1 || td->Ct < 1 || td->Ct > 16)
-        return dressi_fail(ctx, DRESSI_EINVAL, "texture: bad texture shape (Ct must be 1..16)");
+    if (td->Ht < 1 || td->Wt < 1 || td->Ct < 1 || td->Ct > 16 || td->Ht > 32767 || td->Wt > 32767)
+        return dressi_fail(ctx, DRESSI_EINVAL, "texture: bad texture shape (Ht, Wt 1..32767, Ct 1..16)");
     if (td->kind == DRESSI_TEX_CUBE && td->Ht != td->Wt)
         return dressi_fail(ctx, DRESSI_EINVAL, "texture: cube faces must be square");
     if (td->kind == DRESSI_TEX_2D) {
@@ -318,7 +421,13 @@ extern "C" int dressi_texture(dressi_ctx *ctx, const float *tex, const dressi_te
     if (n == 0) return DRESSI_OK;
     if (!out) return dressi_fail(ctx, DRESSI_EINVAL, "texture: null out");
     hipStream_t st = (hipStream_t)stream;
-    DR_LAUNCH("k_tex_fwd", (k_tex_fwd), (int)((n + 255) / 256), 256, 0, st, tex, *td, coord, tri_id, n, out);
+    const int g = (int)((n + 255) / 256);
+    switch (aligned16(tex, out) ? td->Ct : 0) {
+    case 3: DR_LAUNCH("k_tex_fwd", (k_tex_fwd<3>), g, 256, 0, st, tex, *td, coord, tri_id, n, out); break;
+    case 4: DR_LAUNCH("k_tex_fwd", (k_tex_fwd<4>), g, 256, 0, st, tex, *td, coord, tri_id, n, out); break;
+    case 8: DR_LAUNCH("k_tex_fwd", (k_tex_fwd<8>), g, 256, 0, st, tex, *td, coord, tri_id, n, out); break;
+    default: DR_LAUNCH("k_tex_fwd", (k_tex_fwd<0>), g, 256, 0, st, tex, *td, coord, tri_id, n, out); break;
+    }
     return dressi_launch_check(ctx, "texture");
 }
 
@@ -337,33 +446,59 @@ extern "C" int dressi_texture_bwd(dressi_ctx *ctx, const float *tex, const dress
         return dressi_fail(ctx, DRESSI_EINVAL, "texture_bwd: repeat wrap needs at least 3 texels");
     hipStream_t st = (hipStream_t)stream;
     int32_t *inv = nullptr;
+    float *part = nullptr;
     int64_t cells = (int64_t)(td->kind == DRESSI_TEX_CUBE ? 6 : 1) * td->Ht * td->Wt;
     if (grad_tex) {
         Carver c;
         size_t o_inv = c.take(sizeof(int32_t) * (size_t)cells * (S > 0 ? S : 1));
+        size_t o_part = c.take(dressi_invuv_part_bytes(cells, td->Ct, S));
         rc = dressi_scratch(ctx, c.off, st);
         if (rc) return rc;
         inv = at<int32_t>(ctx->scratch, o_inv);
+        part = at<float>(ctx->scratch, o_part);
         if (n > 0) dressi_fill_i32(inv, -1, cells * S, st);
     }
     if (n > 0 && (grad_coord || inv))
-        DR_LAUNCH("k_tex_bwd_pixel", (k_tex_bwd_pixel), (int)((n + 255) / 256), 256, 0, st, tex, *td, coord,
-                  tri_id, npix, S, grad_out, grad_coord, inv);
+    {
+        const int g = (int)((n + 255) / 256);
+        switch (aligned16(tex, grad_out) ? td->Ct : 0) {
+        case 3: DR_LAUNCH("k_tex_bwd_pixel", (k_tex_bwd_pixel<3>), g, 256, 0, st, tex, *td, coord, tri_id, npix, S,
+                          grad_out, grad_coord, inv); break;
+        case 4: DR_LAUNCH("k_tex_bwd_pixel", (k_tex_bwd_pixel<4>), g, 256, 0, st, tex, *td, coord, tri_id, npix, S,
+                          grad_out, grad_coord, inv); break;
+        case 8: DR_LAUNCH("k_tex_bwd_pixel", (k_tex_bwd_pixel<8>), g, 256, 0, st, tex, *td, coord, tri_id, npix, S,
+                          grad_out, grad_coord, inv); break;
+        default: DR_LAUNCH("k_tex_bwd_pixel", (k_tex_bwd_pixel<0>), g, 256, 0, st, tex, *td, coord, tri_id, npix,
+                           S, grad_out, grad_coord, inv); break;
+        }
+    }
     if (grad_tex) {
+        // Small textures (an environment map) have few texel blocks: split the
+        // slices over the grid as well and sum the parts afterwards.
+        int nsplit = 1;
+        nsplit = dressi_invuv_nsplit(cells, S);
+        float *dst = grad_tex;
+        if (nsplit > 1) dst = part;
         dim3 g((unsigned)((td->Wt + IV_T - 1) / IV_T), (unsigned)((td->Ht + IV_T - 1) / IV_T),
-               (unsigned)(td->kind == DRESSI_TEX_CUBE ? 6 : 1));
-        if (td->Ct == 4)
-            DR_LAUNCH("k_invuv_gather", (k_invuv_gather<4>), g, IV_T * IV_T, 0, st, *td, coord, npix, S, inv,
-                      grad_out, grad_tex);
-        else if (td->Ct == 3)
-            DR_LAUNCH("k_invuv_gather", (k_invuv_gather<3>), g, IV_T * IV_T, 0, st, *td, coord, npix, S, inv,
-                      grad_out, grad_tex);
-        else if (td->Ct == 7)
-            DR_LAUNCH("k_invuv_gather", (k_invuv_gather<7>), g, IV_T * IV_T, 0, st, *td, coord, npix, S, inv,
-                      grad_out, grad_tex);
+               (unsigned)((td->kind == DRESSI_TEX_CUBE ? 6 : 1) * nsplit));
+        const int ct = aligned16(grad_out, dst) ? td->Ct : 0;
+        if (ct == 4)
+            DR_LAUNCH("k_invuv_gather", (k_invuv_gather<4>), g, IV_T * IV_T, 0, st, *td, coord, npix, S, nsplit,
+                      inv, grad_out, dst);
+        else if (ct == 3)
+            DR_LAUNCH("k_invuv_gather", (k_invuv_gather<3>), g, IV_T * IV_T, 0, st, *td, coord, npix, S, nsplit,
+                      inv, grad_out, dst);
+        else if (ct == 8)
+            DR_LAUNCH("k_invuv_gather", (k_invuv_gather<8>), g, IV_T * IV_T, 0, st, *td, coord, npix, S, nsplit,
+                      inv, grad_out, dst);
         else
-            DR_LAUNCH("k_invuv_gather", (k_invuv_gather<0>), g, IV_T * IV_T, 0, st, *td, coord, npix, S, inv,
-                      grad_out, grad_tex);
+            DR_LAUNCH("k_invuv_gather", (k_invuv_gather<0>), g, IV_T * IV_T, 0, st, *td, coord, npix, S, nsplit,
+                      inv, grad_out, dst);
+        if (nsplit > 1) {
+            int64_t ne = cells * td->Ct;
+            DR_LAUNCH("k_invuv_reduce", (k_invuv_reduce), (int)((ne + 255) / 256), 256, 0, st, part, nsplit, ne,
+                      grad_tex);
+        }
     }
     return dressi_launch_check(ctx, "texture_bwd");
 }

@@ -9,8 +9,8 @@ here, so a step allocates nothing and can be captured into a hipGraph (the
 analogue of the paper's single recorded command buffer, §3.3.4).
 
 Textures sampled with the same UVs (albedo and normal map) are packed into
-one multi-channel texture so that one sampler pass and one inverse-UV gather
-serve both.
+one 8-channel texture (RGBA, normal XYZ, zero) so that one sampler pass and
+one inverse-UV gather serve both, with aligned float4 texel rows.
 """
 from __future__ import annotations
 
@@ -32,6 +32,15 @@ def _p(t):
 
 def _cp(t, off):
     return None if t is None else C.c_void_p(t.data_ptr() + 4 * off)
+
+
+def pack_textures(albedo: np.ndarray, nmap: np.ndarray | None) -> np.ndarray:
+    """Albedo [Ht,Wt,4] alone, or albedo + normal map [Ht,Wt,3] + one zero
+    channel: 8 channels keep every texel row 32-byte aligned (two float4)."""
+    if nmap is None:
+        return albedo
+    pad = np.zeros(albedo.shape[:2] + (1,), albedo.dtype)
+    return np.concatenate([albedo, nmap, pad], -1)
 
 
 class Step:
@@ -78,8 +87,7 @@ class Step:
         if self.mode != Bd.SHADE_LAMBERT:
             self.tex = p.get("tex", None)
             if self.tex is None:
-                t = scene.tex if scene.nmap is None else np.concatenate([scene.tex, scene.nmap], -1)
-                self.tex = f32(t)
+                self.tex = f32(pack_textures(scene.tex, scene.nmap))
             self.uv = f32(scene.uv)
             self.uv_tris = i32(scene.uv_tris)
         self.Ct = 0 if self.tex is None else self.tex.shape[-1]
@@ -119,7 +127,8 @@ class Step:
         self.g_layer = e(B, K, H, W, 3)
         self.g_dist = e(B, K, H, W) if self.r > 0 else None
         self.g_gbuf = e(B, K, H, W, self.Cv)
-        self.g_samp = e(B, K, H, W, self.Ct) if self.Ct else None
+        # zeroed once: the padding channel of a packed texture is never written
+        self.g_samp = torch.zeros((B, K, H, W, self.Ct), device=dev) if self.Ct else None
         self.g_env_s = e(B, K, H, W, 3) if self.env is not None else None
         self.g_dir = e(B, K, H, W, 3) if self.env is not None else None
         self.g_envtex = torch.empty_like(self.env) if self.env is not None else None
@@ -269,7 +278,7 @@ class Step:
         if self.mode == Bd.SHADE_LAMBERT:
             out["color"] = self.g_vattr[:, 6:9]
         if self.g_tex is not None:
-            out["tex"] = self.g_tex
+            out["tex"] = self.g_tex if self.scene.nmap is None else self.g_tex[..., :7]
         if self.g_envtex is not None:
             out["env"] = self.g_envtex
         return out
@@ -284,8 +293,7 @@ def make_target(scene: Scene, device="cuda", views=None) -> Step:
     if scene.target_color is not None:
         params["color"] = f32(scene.target_color)
     if scene.target_tex is not None:
-        t = scene.target_tex if scene.nmap is None else np.concatenate([scene.target_tex, scene.nmap], -1)
-        params["tex"] = f32(t)
+        params["tex"] = f32(pack_textures(scene.target_tex, scene.nmap))
     st = Step(scene, device, views=views, params=params)
     st.forward()
     return st
