@@ -70,15 +70,15 @@ def scene_for(cfg):
 # HBM traffic per launch from two rocprofv3 counter runs of this script on the
 # headline workload (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch).  Each
 # counter is scaled by its reading for a plain 256 MiB device copy
-# (torch copy_, same runs): FETCH_SIZE read 131,085 KiB for 262,144 KiB moved
+# (torch copy_, same runs): FETCH_SIZE read 131,083.5 KiB for 262,144 KiB moved
 # (x2.0), WRITE_SIZE 262,144 KiB (x1.0).  "sha" fingerprints the kernel's
 # source file when the counters were taken; the figure is reported as null
 # once that file has changed.
-FETCH_SCALE, WRITE_SCALE = 262144.0 / 131085.0, 1.0
+FETCH_SCALE, WRITE_SCALE = 262144.0 / 131083.5, 1.0
 TRAFFIC = {
     "k_invuv_gather": {"src": "paper_2204_01386_amd/csrc/texture.hip",
-                       "sha": "3f2328283ea81af892321598eb6a9939653658f915f731c33d3b38b03b4a59ed",
-                       "fetch_kib": 10125.8125, "write_kib": 16384.0},
+                       "sha": "e09cd5301e3a8b8ae5fd794edc23c805990346a36620a5343ae8769289254dfc",
+                       "fetch_kib": 10130.3125, "write_kib": 16384.0},
 }
 
 
