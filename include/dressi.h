@@ -85,7 +85,8 @@ size_t dressi_scratch_bytes(int B, int V, int T, int H, int W, int K, float r,
 int dressi_check_status(dressi_ctx *ctx, int64_t *needed, void *stream);
 
 /* Kernel timing for measurement: while on, every kernel launch of the library
- * is bracketed by HIP events on its stream.  dressi_profile_start(n) turns it
+ * gets a start/stop HIP event pair that the runtime stamps from the launch's
+ * own dispatch (the kernel's execution time alone).  dressi_profile_start(n) turns it
  * on for up to n launches (0 turns it off); dressi_profile_read waits for the
  * recorded launches, returns their count and fills names[i] (static strings)
  * and ms[i], then starts a new window.  Process-wide; not for use while a

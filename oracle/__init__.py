@@ -92,6 +92,28 @@ def rasterize(pos_clip, tris, H, W, K=1, r=0.0, cull=0):
     return tri_id, hard, bary, dist
 
 
+def rasterize_window(pos_clip, tris, H, W, window, K=1, r=0.0, cull=0):
+    """The layers of the pixels of window = (x0, y0, w, h) of an H x W image
+    (every triangle considered): tri_id [B,K,h,w], hard, bary [..,2], dist."""
+    pc = _f32(pos_clip)
+    if pc.ndim == 2:
+        pc = pc[None]
+    B, V, _ = pc.shape
+    t = _i32(tris)
+    T = t.shape[0]
+    x0, y0, w, h = (int(v) for v in window)
+    tri_id = np.empty((B, K, h, w), np.int32)
+    hard = np.empty((B, K, h, w), np.uint8)
+    bary = np.empty((B, K, h, w, 2), np.float64)
+    dist = np.empty((B, K, h, w), np.float64)
+    f = lib().orc_rasterize_window
+    f.argtypes = [C.c_void_p, C.c_void_p] + [C.c_int] * 6 + [C.c_float, C.c_int] + [C.c_int] * 4 + \
+        [C.c_void_p] * 4
+    _check(f(_p(pc), _p(t), B, V, T, H, W, K, C.c_float(r), cull, x0, y0, w, h,
+             _p(tri_id), _p(hard), _p(bary), _p(dist)), "rasterize_window")
+    return tri_id, hard, bary, dist
+
+
 def resolve(pos_clip, tris, tri_id, hard, snap=True, cull=0):
     pc = _f32(pos_clip)
     if pc.ndim == 2:

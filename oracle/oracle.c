@@ -208,13 +208,18 @@ static void klist_insert(frag *L, int *n, int K, float key, int32_t id)
 static void resolve_one(const otri *s, int px_i, int py_i, int hard, int snap,
                         int H, int W, double *b0, double *b1, double *dist);
 
-int orc_rasterize(const float *pos_clip, const int32_t *tris, int B, int V, int T,
-                  int H, int W, int K, float r, int cull,
-                  int32_t *tri_id, uint8_t *hard, double *bary, double *dist)
+/* The K layers of the pixels of the window [wx0, wx0 + ww) x [wy0, wy0 + wh)
+ * of an H x W image; every triangle is considered, only the window's pixels
+ * are visited and stored ([B,K,wh,ww] outputs).  The full image is the window
+ * (0, 0, W, H). */
+int orc_rasterize_window(const float *pos_clip, const int32_t *tris, int B, int V, int T,
+                         int H, int W, int K, float r, int cull, int wx0, int wy0, int ww, int wh,
+                         int32_t *tri_id, uint8_t *hard, double *bary, double *dist)
 {
     if (B < 0 || V < 0 || T < 0 || H <= 0 || W <= 0 || K < 1 || K > 5) return -1;
     if (!(r >= 0.0f && r <= 1.0f)) return -1;
-    int64_t N = (int64_t)H * W;
+    if (wx0 < 0 || wy0 < 0 || ww <= 0 || wh <= 0 || wx0 + ww > W || wy0 + wh > H) return -1;
+    int64_t N = (int64_t)wh * ww;
     frag *lists = (frag *)malloc(sizeof(frag) * (size_t)(N * K));
     int *cnt = (int *)malloc(sizeof(int) * (size_t)N);
     if (!lists || !cnt) { free(lists); free(cnt); return -2; }
@@ -237,10 +242,10 @@ int orc_rasterize(const float *pos_clip, const int32_t *tris, int B, int V, int 
             int64_t x1 = (int64_t)ceil(xmax / 256.0) + 1 + margin;
             int64_t y0 = (int64_t)floor(ymin / 256.0) - 1 - margin;
             int64_t y1 = (int64_t)ceil(ymax / 256.0) + 1 + margin;
-            if (x0 < 0) x0 = 0;
-            if (y0 < 0) y0 = 0;
-            if (x1 > W - 1) x1 = W - 1;
-            if (y1 > H - 1) y1 = H - 1;
+            if (x0 < wx0) x0 = wx0;
+            if (y0 < wy0) y0 = wy0;
+            if (x1 > wx0 + ww - 1) x1 = wx0 + ww - 1;
+            if (y1 > wy0 + wh - 1) y1 = wy0 + wh - 1;
             for (int64_t y = y0; y <= y1; y++) {
                 for (int64_t x = x0; x <= x1; x++) {
                     int64_t px = SUBPIX * x + SUBPIX / 2, py = SUBPIX * y + SUBPIX / 2;
@@ -259,15 +264,15 @@ int orc_rasterize(const float *pos_clip, const int32_t *tris, int B, int V, int 
                         float h = 0.5f * dn;
                         key = h + 0.5f;
                     }
-                    int64_t p = y * W + x;
+                    int64_t p = (y - wy0) * ww + (x - wx0);
                     klist_insert(lists + p * K, &cnt[p], K, key, t);
                 }
             }
         }
         for (int64_t p = 0; p < N; p++) {
-            int y = (int)(p / W), x = (int)(p % W);
+            int y = wy0 + (int)(p / ww), x = wx0 + (int)(p % ww);
             for (int k = 0; k < K; k++) {
-                int64_t o = (((int64_t)b * K + k) * H + y) * W + x;
+                int64_t o = ((int64_t)b * K + k) * N + p;
                 if (k < cnt[p]) {
                     int32_t t = lists[p * K + k].id;
                     tri_id[o] = t;
@@ -291,6 +296,14 @@ int orc_rasterize(const float *pos_clip, const int32_t *tris, int B, int V, int 
     free(lists);
     free(cnt);
     return 0;
+}
+
+int orc_rasterize(const float *pos_clip, const int32_t *tris, int B, int V, int T,
+                  int H, int W, int K, float r, int cull,
+                  int32_t *tri_id, uint8_t *hard, double *bary, double *dist)
+{
+    return orc_rasterize_window(pos_clip, tris, B, V, T, H, W, K, r, cull, 0, 0, W, H,
+                                tri_id, hard, bary, dist);
 }
 
 /* ------------------------------------------------------------------------ */

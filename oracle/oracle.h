@@ -27,6 +27,9 @@ typedef struct {
 int orc_rasterize(const float *pos_clip, const int32_t *tris, int B, int V, int T,
                   int H, int W, int K, float r, int cull,
                   int32_t *tri_id, uint8_t *hard, double *bary, double *dist);
+int orc_rasterize_window(const float *pos_clip, const int32_t *tris, int B, int V, int T,
+                         int H, int W, int K, float r, int cull, int wx0, int wy0, int ww, int wh,
+                         int32_t *tri_id, uint8_t *hard, double *bary, double *dist);
 int orc_resolve(const float *pos_clip, const int32_t *tris, int B, int V, int T,
                 int H, int W, int K, int cull, int snap,
                 const int32_t *tri_id, const uint8_t *hard, double *bary, double *dist);

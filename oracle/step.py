@@ -57,7 +57,8 @@ def forward(scene, views=None, target=False):
         shade_n = nrm
     else:
         uv = O.interpolate_f32(scene.uv, scene.uv_tris, tid, bary.astype(np.float32))
-        samp = O.texture(tex, uv, tid)
+        wu, wv = scene.extra.get("wrap", (O.WRAP_REPEAT, O.WRAP_CLAMP))
+        samp = O.texture(tex, uv, tid, wrap_u=wu, wrap_v=wv)
         st.update(uv=uv, samp=samp)
         albedo = samp[..., 0:4]
         shade_n = nrm
@@ -114,8 +115,9 @@ def backward(scene, st, target_rgba):
         uv = st["uv"]
         S = tid.shape[0] * tid.shape[1]
         rs = lambda a: a.reshape((S,) + a.shape[2:])
-        g_uv = O.texture_bwd_coord(st["tex"], uv, g_samp, tid)
-        out["tex"] = O.texture_bwd_tex(st["tex"].shape, rs(uv), rs(tid), rs(g_samp))
+        wu, wv = scene.extra.get("wrap", (O.WRAP_REPEAT, O.WRAP_CLAMP))
+        g_uv = O.texture_bwd_coord(st["tex"], uv, g_samp, tid, wrap_u=wu, wrap_v=wv)
+        out["tex"] = O.texture_bwd_tex(st["tex"].shape, rs(uv), rs(tid), rs(g_samp), wrap_u=wu, wrap_v=wv)
         _, g_bary_uv = O.interpolate_bwd(scene.uv, scene.uv_tris, tid, st["bary"], g_uv)
     g_vattr, g_bary = O.interpolate_bwd(st["vattr"], tris, tid, st["bary"], g_gbuf)
     g_bary = g_bary + g_bary_uv

@@ -98,8 +98,8 @@ class Step:
                 self.env = f32(scene.env)
         self.desc = Bd.TexDesc(0, 0, 0, 0, 0, 0)
         if self.tex is not None:
-            self.desc = Bd.TexDesc(Bd.TEX_2D, self.tex.shape[0], self.tex.shape[1], self.Ct,
-                                   Bd.WRAP_REPEAT, Bd.WRAP_CLAMP)
+            wu, wv = scene.extra.get("wrap", (Bd.WRAP_REPEAT, Bd.WRAP_CLAMP))
+            self.desc = Bd.TexDesc(Bd.TEX_2D, self.tex.shape[0], self.tex.shape[1], self.Ct, wu, wv)
         if self.env is not None:
             self.env_desc = Bd.TexDesc(Bd.TEX_CUBE, self.env.shape[1], self.env.shape[2],
                                        self.env.shape[3], Bd.WRAP_CLAMP, Bd.WRAP_CLAMP)
@@ -148,6 +148,27 @@ class Step:
         self.frag_index = torch.empty(nbytes, dtype=torch.uint8, device=dev)
         self._fin = self._frag_in()
         self._fin_dir = self._frag_in(with_env=False)
+        self._calibrate_bins()
+
+    def _calibrate_bins(self):
+        """Rasterizes once and grows the tile-bin capacity until no tile
+        overflows (dense or strongly overlapping geometry), so that later
+        steps, captured or not, need no check."""
+        h, st = self.ctx.handle, self._s()
+        for _ in range(4):
+            self._chk(_lib.dressi_transform(h, _p(self.pos), _p(self.mvp), self.B, self.V, _p(self.pos_clip), st),
+                      "transform")
+            self._chk(_lib.dressi_rasterize(h, _p(self.pos_clip), _p(self.tris), self.B, self.V, self.T, self.H,
+                                            self.W, self.K, self.r, 0, _p(self.tri_id), _p(self.bary),
+                                            _p(self.dist), st), "rasterize")
+            need = self.ctx.check_status()
+            if need <= 0:
+                return
+            cap = 1
+            while cap < need * 5 // 4:
+                cap <<= 1
+            self.ctx.reserve(0, cap)
+        raise RuntimeError("tile bins still overflow after growing them")
 
     # ------------------------------------------------------------------
     def _frag_in(self, with_env=True):

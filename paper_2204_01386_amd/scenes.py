@@ -156,6 +156,83 @@ def torus(nu: int, nv: int, R=0.7, r=0.3):
     return pos, tris
 
 
+def grid_tris(nu: int, nv: int):
+    """Triangles of an nu x nv quad grid wrapping in both directions (vertex
+    (i, j) has index i * nv + j), two per quad, vectorised."""
+    i, j = np.meshgrid(np.arange(nu), np.arange(nv), indexing="ij")
+    a = i * nv + j
+    b = ((i + 1) % nu) * nv + j
+    c = ((i + 1) % nu) * nv + (j + 1) % nv
+    d = i * nv + (j + 1) % nv
+    t = np.stack([np.stack([a, b, c], -1), np.stack([a, c, d], -1)], 2)
+    return t.reshape(-1, 3).astype(np.int32)
+
+
+def smooth_noise_edges(rng, tris, V, iters=5):
+    """N(0,1) per vertex smoothed by `iters` Jacobi neighbour-averaging passes
+    (neighbours from the unique edges; vectorised for large meshes)."""
+    n = rng.standard_normal(V)
+    e = np.concatenate([tris[:, [0, 1]], tris[:, [1, 2]], tris[:, [2, 0]]])
+    e = np.concatenate([e, e[:, ::-1]]).astype(np.int64)
+    e = np.unique(e[:, 0] * V + e[:, 1])
+    src, dst = e // V, e % V
+    deg = np.bincount(src, minlength=V).astype(np.float64)
+    for _ in range(iters):
+        n = np.bincount(src, weights=n[dst], minlength=V) / np.maximum(deg, 1)
+    return n
+
+
+def torus_knot(nu: int = 2048, nv: int = 256, p: int = 2, q: int = 3, radius: float = 0.15,
+               seed: int = 0, amp: float = 0.05):
+    """(p,q) torus-knot tube: core curve ((2 + cos qt) cos pt, (2 + cos qt) sin pt,
+    sin qt), Frenet frame, tube radius radius * (1 + amp * smoothed N(0,1)) per
+    vertex, scaled to fit the unit sphere.  nu x nv grid wrapping both ways:
+    V = nu nv, T = 2 nu nv, outward counter-clockwise.  Per-corner UVs
+    (8 i / nu, j / nv) on an (nu+1) x (nv+1) UV grid (seams split), repeat."""
+    t = 2 * math.pi * np.arange(nu) / nu
+    r = 2.0 + np.cos(q * t)
+    c = np.stack([r * np.cos(p * t), r * np.sin(p * t), np.sin(q * t)], -1)
+    dr = -q * np.sin(q * t)
+    d1 = np.stack([dr * np.cos(p * t) - p * r * np.sin(p * t),
+                   dr * np.sin(p * t) + p * r * np.cos(p * t), q * np.cos(q * t)], -1)
+    ddr = -q * q * np.cos(q * t)
+    d2 = np.stack([ddr * np.cos(p * t) - 2 * p * dr * np.sin(p * t) - p * p * r * np.cos(p * t),
+                   ddr * np.sin(p * t) + 2 * p * dr * np.cos(p * t) - p * p * r * np.sin(p * t),
+                   -q * q * np.sin(q * t)], -1)
+    T_ = d1 / np.linalg.norm(d1, axis=1, keepdims=True)
+    N_ = d2 - (d2 * T_).sum(1, keepdims=True) * T_
+    N_ /= np.linalg.norm(N_, axis=1, keepdims=True)
+    B_ = np.cross(T_, N_)
+    tris = grid_tris(nu, nv)
+    V = nu * nv
+    rng = np.random.default_rng(seed)
+    rad = radius * (1.0 + amp * smooth_noise_edges(rng, tris, V)).reshape(nu, nv)
+    phi = 2 * math.pi * np.arange(nv) / nv
+    ring = np.cos(phi)[None, :, None] * N_[:, None, :] + np.sin(phi)[None, :, None] * B_[:, None, :]
+    pos = (c[:, None, :] + rad[:, :, None] * ring).reshape(-1, 3)
+    pos = pos / np.linalg.norm(pos, axis=1).max()
+    # outward: away from the (equally scaled) core curve
+    ctr = np.repeat(c / np.linalg.norm(c[:, None, :] + rad[:, :, None] * ring, axis=2).max(), nv, 0)
+    fn = np.cross(pos[tris[:, 1]] - pos[tris[:, 0]], pos[tris[:, 2]] - pos[tris[:, 0]])
+    out = pos[tris].mean(1) - ctr[tris[:, 0]]
+    if (fn * out).sum(1).mean() < 0:
+        tris = tris[:, [0, 2, 1]].copy()
+    # UVs: corner (i, j) -> (8 i / nu, j / nv) with i, j unwrapped at the seams
+    iu = np.arange(nu + 1)
+    jv = np.arange(nv + 1)
+    U, Vv = np.meshgrid(8.0 * iu / nu, jv / nv, indexing="ij")
+    uv = np.stack([U, Vv], -1).reshape(-1, 2)
+    i, j = np.meshgrid(np.arange(nu), np.arange(nv), indexing="ij")
+    a = i * (nv + 1) + j
+    b = (i + 1) * (nv + 1) + j
+    cc = (i + 1) * (nv + 1) + j + 1
+    d = i * (nv + 1) + j + 1
+    uv_tris = np.stack([np.stack([a, b, cc], -1), np.stack([a, cc, d], -1)], 2).reshape(-1, 3)
+    if not np.array_equal(tris, grid_tris(nu, nv)):
+        uv_tris = uv_tris[:, [0, 2, 1]]
+    return pos.astype(np.float32), tris, uv.astype(np.float32), uv_tris.astype(np.int32)
+
+
 # --------------------------------------------------------------------------
 # textures
 # --------------------------------------------------------------------------
@@ -176,15 +253,14 @@ def value_noise(H: int, W: int, C: int, seed: int, octaves: int = 4, base: int =
         sy, sx = ty * ty * (3 - 2 * ty), tx * tx * (3 - 2 * tx)
         y1, x1 = (y0 + 1) % n, (x0 + 1) % n
         y0, x0 = y0 % n, x0 % n
-        a = lat[y0][:, x0]
-        b = lat[y0][:, x1]
-        c = lat[y1][:, x0]
-        d = lat[y1][:, x1]
-        sx_ = sx[None, :, None]
-        sy_ = sy[:, None, None]
-        top = a + (b - a) * sx_
-        bot = c + (d - c) * sx_
-        out += (top + (bot - top) * sy_) * (0.5 ** o)
+        # interpolate every lattice row along x once, then between rows along y
+        a = lat[:, x0]
+        lx = a + (lat[:, x1] - a) * sx[None, :, None]          # [n, W, C]
+        for r0 in range(0, H, 256):                            # row bands bound the temporaries
+            r1 = min(H, r0 + 256)
+            top = lx[y0[r0:r1]]
+            bot = lx[y1[r0:r1]]
+            out[r0:r1] += (top + (bot - top) * sy[r0:r1, None, None]) * (0.5 ** o)
     lo = out.min(axis=(0, 1), keepdims=True)
     hi = out.max(axis=(0, 1), keepdims=True)
     return ((out - lo) / np.maximum(hi - lo, 1e-12)).astype(np.float32)
@@ -336,6 +412,23 @@ def config3(seed: int = 0, n_views: int = 16, H: int = 512, subdiv: int = 6,
     s.nmap = normal_map(tex_size, tex_size, seed + 7)
     s.env = cube_env_map(env_size, seed + 11)
     s.extra["tangent"] = sphere_tangents(s.pos)
+    return s
+
+
+def config5(seed: int = 0, n_views: int = 8, H: int = 2048, nu: int = 2048, nv: int = 256,
+            tex_size: int = 4096) -> Scene:
+    """(2,3) torus-knot tube, 2048 x 256 grid (1,048,576 triangles, 524,288
+    vertices), per-corner UVs (8 i/2048, j/256) on a 4096^2 RGBA fp32 value-noise
+    texture (repeat), 8 cameras as in config 3 at 2048^2, HardSoftRas K=3,
+    r=0.01, Phong.  Target: tube noise seed+1, texture seed+1."""
+    p, tris, uv, uv_tris = torus_knot(nu, nv, seed=seed)
+    tp, _, _, _ = torus_knot(nu, nv, seed=seed + 1)
+    eyes = camera_ring(n_views, seed)
+    s = Scene(f"torus-knot-{nu}x{nv}-{n_views}x{H}-hsr", p, tris, view_proj(eyes), eyes.astype(np.float32),
+              H, H, 3, 0.01, "phong", uv=uv, uv_tris=uv_tris,
+              tex=value_noise(tex_size, tex_size, 4, seed), target_pos=tp,
+              target_tex=value_noise(tex_size, tex_size, 4, seed + 1))
+    s.extra["wrap"] = (0, 0)   # repeat in u and v
     return s
 
 

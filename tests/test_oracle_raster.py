@@ -344,3 +344,18 @@ def test_rasterize_bwd_finite_differences(K, r):
             fd[0, v, c] = (loss(pp) - loss(pm)) / step
     assert np.all(ana[0, :, 2] == 0.0)
     assert rel_err(ana, fd) < 1e-3
+
+
+def test_window_equals_crop_of_full_image():
+    """The windowed rasterizer (used for sampled checks of large images) visits
+    only the window's pixels but considers every triangle: its layers are the
+    crop of the full image's."""
+    from paper_2204_01386_amd import scenes
+    s = scenes.config1()
+    pc = oracle.transform_f32(s.pos, s.mvp)
+    full = oracle.rasterize(pc, s.tris, 128, 128, K=3, r=0.05)
+    for win in [(0, 0, 128, 128), (20, 30, 50, 40), (127, 0, 1, 128), (60, 60, 7, 3)]:
+        x0, y0, w, h = win
+        part = oracle.rasterize_window(pc, s.tris, 128, 128, win, K=3, r=0.05)
+        for a, b in zip(full, part):
+            assert np.array_equal(a[:, :, y0:y0 + h, x0:x0 + w], b)
