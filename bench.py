@@ -33,7 +33,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3])
+    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 5])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--profile-steps", type=int, default=20)
@@ -54,8 +54,11 @@ def scene_for(cfg):
     if cfg == 2:
         return scenes.config2(), ("noisy icosphere s6 (40,962 v, 81,920 t), 1 view 512x512, "
                                   "1024x1024 RGBA fp32 texture, K=1, Phong")
-    return scenes.config3(), ("noisy icosphere s6 (81,920 t), 16 views 512x512, 1024^2 RGBA texture + "
-                              "1024^2 normal map, 6x128^2 env map, HardSoftRas K=3 r=0.01, Phong+env")
+    if cfg == 3:
+        return scenes.config3(), ("noisy icosphere s6 (81,920 t), 16 views 512x512, 1024^2 RGBA texture + "
+                                  "1024^2 normal map, 6x128^2 env map, HardSoftRas K=3 r=0.01, Phong+env")
+    return scenes.config5(), ("torus-knot tube (524,288 v, 1,048,576 t), 8 views 2048x2048, 4096^2 RGBA "
+                              "texture, HardSoftRas K=3 r=0.01, Phong")
 
 
 # ---------------------------------------------------------------------------
