@@ -47,6 +47,7 @@ extern "C" {
 /* texture kinds and wrap modes */
 #define DRESSI_TEX_2D 0   /* tex [Ht,Wt,Ct], coord (u,v); u along columns, v along rows */
 #define DRESSI_TEX_CUBE 1 /* tex [6,S,S,Ct] faces +X,-X,+Y,-Y,+Z,-Z; coord = direction */
+#define DRESSI_TEX_2D_ARRAY 2 /* tex [L,Ht,Wt,Ct]; coord (u,v); layer from the triangle */
 #define DRESSI_WRAP_REPEAT 0
 #define DRESSI_WRAP_CLAMP 1
 
@@ -59,9 +60,13 @@ extern "C" {
 typedef struct dressi_ctx dressi_ctx;
 
 typedef struct {
-    int kind;           /* DRESSI_TEX_2D or DRESSI_TEX_CUBE (then Ht == Wt == S) */
+    int kind;           /* DRESSI_TEX_2D, DRESSI_TEX_CUBE (Ht == Wt == S) or DRESSI_TEX_2D_ARRAY */
     int Ht, Wt, Ct;     /* texels per column, per row (1..32767), channels (1..16) */
-    int wrap_u, wrap_v; /* 2D only; repeat needs Wt (Ht) >= 3                     */
+    int wrap_u, wrap_v; /* 2D and arrays; repeat needs Wt (Ht) >= 3               */
+    int layers;         /* arrays: number of layers                              */
+    const int32_t *tri_layer; /* arrays: device [T] layer of each triangle; a
+                                 fragment samples its triangle's layer (tri_id
+                                 is then required)                              */
 } dressi_tex_desc;
 
 /* ----------------------------------------------------------------------------
@@ -114,7 +119,7 @@ int dressi_profile_read(const char **names, float *ms, int max);
  *   dist   [B,K,H,W] float  signed distance to the triangle in screen units,
  *          + for hard and - for soft fragments (the sign bit carries the
  *          flag, also at 0), 0 if empty.  Required iff r > 0, else may be NULL.
- * Limits: T < 2^21 - 1, |vertex| within a +-16384-pixel guard band, w > 0
+ * Limits: T < 2^31 - 1, |vertex| within a +-16384-pixel guard band, w > 0
  * for all three vertices of a rasterized triangle (others are dropped).
  * ------------------------------------------------------------------------- */
 int dressi_rasterize(dressi_ctx *ctx, const float *pos_clip, const int32_t *tris,
@@ -135,6 +140,24 @@ int dressi_rasterize_bwd(dressi_ctx *ctx, const float *pos_clip, const int32_t *
                          const int32_t *tri_id, const float *grad_bary, const float *grad_dist,
                          const void *frag_index, const int32_t *adj, float *grad_pos_clip,
                          void *stream);
+
+/* Uneven batches, hard rasterization (r = 0): triangle t of the concatenated
+ * meshes belongs to view tri_view[t], drawn in the rectangle
+ * views[4*v .. 4*v+3] = (x0, y0, W_v, H_v) (device int32) of one H x W image.
+ * Each triangle is snapped in its own view's frame (exactly as a standalone
+ * W_v x H_v render) and then moved by the integer offset; it covers only
+ * pixels of its rectangle.  Outputs as dressi_rasterize with B = 1:
+ * tri_id [K,H,W] (global triangle ids), bary [K,H,W,2].  The backward gives
+ * grad_pos_clip [V,4] of the concatenated vertices. */
+int dressi_rasterize_batched(dressi_ctx *ctx, const float *pos_clip, const int32_t *tris,
+                             const int32_t *tri_view, const int32_t *views, int n, int V, int T,
+                             int H, int W, int K, int cull, int32_t *tri_id, float *bary,
+                             void *stream);
+int dressi_rasterize_batched_bwd(dressi_ctx *ctx, const float *pos_clip, const int32_t *tris,
+                                 const int32_t *tri_view, const int32_t *views, int n, int V, int T,
+                                 int H, int W, int K, int cull, const int32_t *tri_id,
+                                 const float *grad_bary, const void *frag_index, const int32_t *adj,
+                                 float *grad_pos_clip, void *stream);
 
 /* ----------------------------------------------------------------------------
  * Reusable index structures for the deterministic backward reductions.
@@ -242,6 +265,17 @@ int dressi_transform(dressi_ctx *ctx, const float *pos, const float *mvp, int B,
 int dressi_transform_bwd(dressi_ctx *ctx, const float *mvp, int B, int V, const float *grad_clip,
                          float *grad_pos, void *stream);
 
+/* Uneven batches (many meshes, each seen by its own camera at its own
+ * resolution, drawn into rectangles of one image so that every stage runs as
+ * one launch for the whole batch).  The meshes are concatenated: vertex v
+ * belongs to view vert_view[v] and is transformed by mvp[vert_view[v]]
+ * ([n,4,4] row-major); pos [V,3] -> pos_clip [V,4].  The backward gives
+ * grad_pos [V,3] = M^T grad_clip per vertex with its own view's matrix. */
+int dressi_transform_batched(dressi_ctx *ctx, const float *pos, const int32_t *vert_view,
+                             const float *mvp, int V, float *pos_clip, void *stream);
+int dressi_transform_batched_bwd(dressi_ctx *ctx, const float *mvp, const int32_t *vert_view, int V,
+                                 const float *grad_clip, float *grad_pos, void *stream);
+
 /* adj: the mesh adjacency (dressi_adjacency) or NULL to build it internally.
  * Per-vertex attribute rows out[v] = (n_v, p_v[, extra_v]) with C = 6 or 9,
  * n_v = normalize(sum of (p1-p0) x (p2-p0) over the faces of v) (the
@@ -270,6 +304,8 @@ typedef struct {
     const float *albedo; int albedo_stride;   /* albedo rgb or rgba                    */
     int albedo_channels;                      /* 3 or 4 (Phong modes need 4)           */
     const float *env; int env_stride;         /* environment sample (PHONG_ENV)        */
+    const int32_t *tri_eye;                   /* uneven batches: camera of each triangle
+                                                 (index into eye), or NULL: eye[i / Npv] */
 } dressi_frag_in;
 
 typedef struct {
@@ -282,7 +318,7 @@ typedef struct {
 } dressi_frag_grad;
 
 /* Deferred shading of N = B*Npv fragments (view b = i / Npv, eye[b] its camera
- * position, light direction (1,1,2)/sqrt(6), white).  The shading normal is
+ * position, or eye[in->tri_eye[tri_id[i]]] in an uneven batch; light direction (1,1,2)/sqrt(6), white).  The shading normal is
  * normalize(normal), or, with tangent and nmap, normalize(m_x t^ + m_y b^ +
  * m_z n^) with t^ = normalize(t - (t.n^) n^), b^ = n^ x t^.  Writes, when
  * non-NULL: dir [N,3] = reflect(-v^, n') (the environment lookup direction)
@@ -299,12 +335,16 @@ int dressi_shade_bwd(dressi_ctx *ctx, int mode, const dressi_frag_in *in, const 
                      const int32_t *tri_id, int B, int64_t Npv, const float *grad_color,
                      const float *grad_dir, const dressi_frag_grad *grad, void *stream);
 
-/* L = mean over B*H*W*4 of ((color, sil) - target)^2.  color [B,H,W,3],
- * sil [B,H,W], target [B,H,W,4]; writes loss [1] (device, fixed-order
- * reduction) and, when non-NULL, grad_color and grad_sil of L. */
+/* L = mean over B*H*W*4 of ((color, sil) - target)^2, or, with a per-pixel
+ * weight [B,H,W] (NULL = uniform), L = sum over pixels of weight * sum over
+ * the 4 channels of the squared difference (an uneven batch passes
+ * 1 / (4 H_i W_i) for the pixels of view i and 0 elsewhere: the sum of the
+ * per-view means).  color [B,H,W,3], sil [B,H,W], target [B,H,W,4]; writes
+ * loss [1] (device, fixed-order reduction) and, when non-NULL, grad_color and
+ * grad_sil of L. */
 int dressi_loss_l2(dressi_ctx *ctx, const float *color, const float *sil, const float *target,
-                   int B, int H, int W, float *loss, float *grad_color, float *grad_sil,
-                   void *stream);
+                   const float *weight, int B, int H, int W, float *loss, float *grad_color,
+                   float *grad_sil, void *stream);
 
 #ifdef __cplusplus
 }

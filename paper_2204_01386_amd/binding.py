@@ -25,7 +25,7 @@ if not os.path.exists(LIB_PATH):
 
 _lib = C.CDLL(LIB_PATH)
 
-TEX_2D, TEX_CUBE = 0, 1
+TEX_2D, TEX_CUBE, TEX_2D_ARRAY = 0, 1, 2
 WRAP_REPEAT, WRAP_CLAMP = 0, 1
 BLEND_HSR, BLEND_AA, BLEND_SOFTRAS, BLEND_HARD = 0, 1, 2, 3
 
@@ -34,7 +34,7 @@ STATUS = {0: "ok", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "EOVERFLOW"}
 
 class TexDesc(C.Structure):
     _fields_ = [("kind", C.c_int), ("Ht", C.c_int), ("Wt", C.c_int), ("Ct", C.c_int),
-                ("wrap_u", C.c_int), ("wrap_v", C.c_int)]
+                ("wrap_u", C.c_int), ("wrap_v", C.c_int), ("layers", C.c_int), ("tri_layer", C.c_void_p)]
 
 
 _vp, _i, _f, _i64, _sz = C.c_void_p, C.c_int, C.c_float, C.c_int64, C.c_size_t
@@ -47,7 +47,7 @@ class FragIn(C.Structure):
     _fields_ = [("normal", _vp), ("normal_stride", _i), ("pos", _vp), ("pos_stride", _i),
                 ("tangent", _vp), ("tangent_stride", _i), ("nmap", _vp), ("nmap_stride", _i),
                 ("albedo", _vp), ("albedo_stride", _i), ("albedo_channels", _i),
-                ("env", _vp), ("env_stride", _i)]
+                ("env", _vp), ("env_stride", _i), ("tri_eye", _vp)]
 
 
 class FragGrad(C.Structure):
@@ -77,7 +77,12 @@ _SIG = {
     "dressi_fragment_index": [_vp, _vp, _i, _i, _i, _i, _i, _vp, _vp],
     "dressi_shade": [_vp, _i, _vp, _vp, _vp, _i, _i64, _vp, _vp, _vp],
     "dressi_shade_bwd": [_vp, _i, _vp, _vp, _vp, _i, _i64, _vp, _vp, _vp, _vp],
-    "dressi_loss_l2": [_vp, _vp, _vp, _vp, _i, _i, _i, _vp, _vp, _vp, _vp],
+    "dressi_loss_l2": [_vp, _vp, _vp, _vp, _vp, _i, _i, _i, _vp, _vp, _vp, _vp],
+    "dressi_transform_batched": [_vp, _vp, _vp, _vp, _i, _vp, _vp],
+    "dressi_transform_batched_bwd": [_vp, _vp, _vp, _i, _vp, _vp, _vp],
+    "dressi_rasterize_batched": [_vp, _vp, _vp, _vp, _vp, _i, _i, _i, _i, _i, _i, _i, _vp, _vp, _vp],
+    "dressi_rasterize_batched_bwd": [_vp, _vp, _vp, _vp, _vp, _i, _i, _i, _i, _i, _i, _i, _vp, _vp, _vp, _vp,
+                                     _vp, _vp],
 }
 for _name, _args in _SIG.items():
     fn = getattr(_lib, _name)
@@ -241,7 +246,11 @@ def dressi_interpolate_bwd(attr, attr_tris, tri_id, bary, grad_out, need_attr=Tr
     return ga, gb
 
 
-def _desc(tex, kind, wrap_u, wrap_v):
+def _desc(tex, kind, wrap_u, wrap_v, tri_layer=None):
+    if kind == TEX_2D_ARRAY:
+        L, Ht, Wt, Ct = tex.shape
+        _need(tri_layer, torch.int32, "tri_layer")
+        return TexDesc(kind, Ht, Wt, Ct, wrap_u, wrap_v, L, tri_layer.data_ptr())
     if kind == TEX_CUBE:
         _, Ht, Wt, Ct = tex.shape
     else:
@@ -249,11 +258,11 @@ def _desc(tex, kind, wrap_u, wrap_v):
     return TexDesc(kind, Ht, Wt, Ct, wrap_u, wrap_v)
 
 
-def dressi_texture(tex, coord, tri_id, kind=TEX_2D, wrap_u=WRAP_REPEAT, wrap_v=WRAP_CLAMP):
+def dressi_texture(tex, coord, tri_id, kind=TEX_2D, wrap_u=WRAP_REPEAT, wrap_v=WRAP_CLAMP, tri_layer=None):
     """coord [S,H,W,2|3], tri_id [S,H,W] (or [B,K,H,W] flattened to S=B*K)."""
     _need(tex, torch.float32, "tex")
     _need(coord, torch.float32, "coord")
-    d = _desc(tex, kind, wrap_u, wrap_v)
+    d = _desc(tex, kind, wrap_u, wrap_v, tri_layer)
     lead = coord.shape[:-1]
     H, W = lead[-2], lead[-1]
     S = coord.numel() // (coord.shape[-1] * H * W)
@@ -266,9 +275,9 @@ def dressi_texture(tex, coord, tri_id, kind=TEX_2D, wrap_u=WRAP_REPEAT, wrap_v=W
 
 
 def dressi_texture_bwd(tex, coord, tri_id, grad_out, kind=TEX_2D, wrap_u=WRAP_REPEAT,
-                       wrap_v=WRAP_CLAMP, need_tex=True, need_coord=True):
+                       wrap_v=WRAP_CLAMP, need_tex=True, need_coord=True, tri_layer=None):
     _need(grad_out, torch.float32, "grad_out")
-    d = _desc(tex, kind, wrap_u, wrap_v)
+    d = _desc(tex, kind, wrap_u, wrap_v, tri_layer)
     lead = coord.shape[:-1]
     H, W = lead[-2], lead[-1]
     S = coord.numel() // (coord.shape[-1] * H * W)
@@ -323,6 +332,56 @@ def dressi_transform(pos, mvp):
     ctx = context(pos.device.index)
     ctx.check(_lib.dressi_transform(ctx.handle, _ptr(pos), _ptr(mvp), B, V, _ptr(out), _stream()),
               "dressi_transform")
+    return out
+
+
+def dressi_transform_batched(pos, vert_view, mvp):
+    """pos [V,3], vert_view [V] int32, mvp [n,4,4] -> pos_clip [V,4]."""
+    _need(pos, torch.float32, "pos")
+    _need(vert_view, torch.int32, "vert_view")
+    V = pos.shape[0]
+    out = torch.empty((V, 4), dtype=torch.float32, device=pos.device)
+    ctx = context(pos.device.index)
+    ctx.check(_lib.dressi_transform_batched(ctx.handle, _ptr(pos), _ptr(vert_view), _ptr(mvp), V, _ptr(out),
+                                            _stream()), "dressi_transform_batched")
+    return out
+
+
+def dressi_transform_batched_bwd(mvp, vert_view, grad_clip):
+    V = grad_clip.shape[0]
+    out = torch.empty((V, 3), dtype=torch.float32, device=grad_clip.device)
+    ctx = context(grad_clip.device.index)
+    ctx.check(_lib.dressi_transform_batched_bwd(ctx.handle, _ptr(mvp), _ptr(vert_view), V, _ptr(grad_clip),
+                                                _ptr(out), _stream()), "dressi_transform_batched_bwd")
+    return out
+
+
+def dressi_rasterize_batched(pos_clip, tris, tri_view, views, H, W, K=1, cull=0):
+    """pos_clip [V,4], tris [T,3], tri_view [T] int32, views [n,4] int32 (x0, y0, W, H)
+    -> tri_id [1,K,H,W], bary [1,K,H,W,2]."""
+    _need(pos_clip, torch.float32, "pos_clip")
+    _need(views, torch.int32, "views")
+    V, T, n = pos_clip.shape[0], tris.shape[0], views.shape[0]
+    dev = pos_clip.device
+    tid = torch.empty((1, K, H, W), dtype=torch.int32, device=dev)
+    bary = torch.empty((1, K, H, W, 2), dtype=torch.float32, device=dev)
+    ctx = context(dev.index)
+    ctx.check(_lib.dressi_rasterize_batched(ctx.handle, _ptr(pos_clip), _ptr(tris), _ptr(tri_view), _ptr(views),
+                                            n, V, T, H, W, K, cull, _ptr(tid), _ptr(bary), _stream()),
+              "dressi_rasterize_batched")
+    return tid, bary
+
+
+def dressi_rasterize_batched_bwd(pos_clip, tris, tri_view, views, tri_id, grad_bary, cull=0, frag_index=None,
+                                 adj=None):
+    V, T, n = pos_clip.shape[0], tris.shape[0], views.shape[0]
+    _, K, H, W = tri_id.shape
+    out = torch.empty((V, 4), dtype=torch.float32, device=pos_clip.device)
+    ctx = context(pos_clip.device.index)
+    ctx.check(_lib.dressi_rasterize_batched_bwd(ctx.handle, _ptr(pos_clip), _ptr(tris), _ptr(tri_view),
+                                                _ptr(views), n, V, T, H, W, K, cull, _ptr(tri_id), _ptr(grad_bary),
+                                                _ptr(frag_index), _ptr(adj), _ptr(out), _stream()),
+              "dressi_rasterize_batched_bwd")
     return out
 
 
@@ -413,12 +472,12 @@ def dressi_shade_bwd(mode, fin, eye, tri_id, grad_color, grad_dir, fgrad):
               "dressi_shade_bwd")
 
 
-def dressi_loss_l2(color, sil, target, loss=None, grad_color=None, grad_sil=None):
+def dressi_loss_l2(color, sil, target, loss=None, grad_color=None, grad_sil=None, weight=None):
     B, H, W = sil.shape
     if loss is None:
         loss = torch.empty(1, dtype=torch.float32, device=sil.device)
     ctx = context(sil.device.index)
-    ctx.check(_lib.dressi_loss_l2(ctx.handle, _ptr(color), _ptr(sil), _ptr(target), B, H, W,
+    ctx.check(_lib.dressi_loss_l2(ctx.handle, _ptr(color), _ptr(sil), _ptr(target), _ptr(weight), B, H, W,
                                   _ptr(loss), _ptr(grad_color), _ptr(grad_sil), _stream()),
               "dressi_loss_l2")
     return loss

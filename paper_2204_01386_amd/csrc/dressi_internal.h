@@ -171,10 +171,26 @@ __device__ __forceinline__ bool dr_snap(float c, float w, float half, bool is_y,
 
 __device__ __forceinline__ int floor_div256(int v) { return v >> 8; }  // arithmetic shift floors
 
-// Builds the record of triangle `tv` (three vertex ids) for a view.  `margin`
-// extends the pixel bbox (soft reach).  cull = 1 drops faces clockwise in NDC.
+// Views of an uneven batch: triangle t belongs to view tri_view[t], drawn in
+// the rectangle views[v] = (x0, y0, W, H) of one image.  A null tri_view
+// means one view covering the whole H x W image.
+struct Viewports {
+    const int32_t *tri_view;
+    const int4 *views;
+};
+
+__device__ __forceinline__ int4 dr_viewport(const Viewports &vp, int t, int H, int W) {
+    if (!vp.tri_view) return make_int4(0, 0, W, H);
+    return vp.views[vp.tri_view[t]];
+}
+
+// Builds the record of triangle `tv` (three vertex ids) for a view of H x W
+// pixels placed at pixel (ox, oy) of the image (0, 0 for a whole image):
+// coordinates are snapped in the view's own frame, then moved by the integer
+// offset, and the boxes are clamped to the view.  `margin` extends the pixel
+// bbox (soft reach).  cull = 1 drops faces clockwise in NDC.
 __device__ __forceinline__ TriSetup dr_setup(const float4 *pc, int v0, int v1, int v2, int H,
-                                             int W, int cull, int margin) {
+                                             int W, int ox, int oy, int cull, int margin) {
     TriSetup s;
     s.meta = 0;
     s.box0 = 1;      // empty box (x0 = 1 > x1 = 0)
@@ -193,6 +209,8 @@ __device__ __forceinline__ TriSetup dr_setup(const float4 *pc, int v0, int v1, i
         if (!(p[i].w > 0.0f)) return s;
         if (!dr_snap(p[i].x, p[i].w, hw, false, X[i])) return s;
         if (!dr_snap(p[i].y, p[i].w, hh, true, Y[i])) return s;
+        X[i] += DRESSI_SUBPIX * ox;
+        Y[i] += DRESSI_SUBPIX * oy;
     }
     int64_t A2 = (int64_t)(X[1] - X[0]) * (int64_t)(Y[2] - Y[0]) -
                  (int64_t)(X[2] - X[0]) * (int64_t)(Y[1] - Y[0]);
@@ -227,8 +245,8 @@ __device__ __forceinline__ TriSetup dr_setup(const float4 *pc, int v0, int v1, i
     int y1 = floor_div256(ymax - 128) + margin;
     {
         int hx0 = x0 + margin, hx1 = x1 - margin, hy0 = y0 + margin, hy1 = y1 - margin;
-        hx0 = min(max(hx0, -1), W); hx1 = min(max(hx1, -1), W);
-        hy0 = min(max(hy0, -1), H); hy1 = min(max(hy1, -1), H);
+        hx0 = min(max(hx0, ox - 1), ox + W); hx1 = min(max(hx1, ox - 1), ox + W);
+        hy0 = min(max(hy0, oy - 1), oy + H); hy1 = min(max(hy1, oy - 1), oy + H);
         s.hbox0 = (hx0 & 0xffff) | (hx1 << 16);
         s.hbox1 = (hy0 & 0xffff) | (hy1 << 16);
         float zmin = fminf(fminf(s.zn[0], s.zn[1]), s.zn[2]);
@@ -241,8 +259,8 @@ __device__ __forceinline__ TriSetup dr_setup(const float4 *pc, int v0, int v1, i
             s.elen[i] = sqrtf((float)(ex * ex + ey * ey));
         }
     }
-    x0 = max(x0, 0); y0 = max(y0, 0);
-    x1 = min(x1, W - 1); y1 = min(y1, H - 1);
+    x0 = max(x0, ox); y0 = max(y0, oy);
+    x1 = min(x1, ox + W - 1); y1 = min(y1, oy + H - 1);
     if (x0 > x1 || y0 > y1) return s;
     s.box0 = x0 | (x1 << 16);
     s.box1 = y0 | (y1 << 16);
@@ -253,9 +271,9 @@ __device__ __forceinline__ TriSetup dr_setup(const float4 *pc, int v0, int v1, i
 __device__ __forceinline__ int dr_corner(int meta, int i) { return (meta >> (4 + 2 * i)) & 3; }
 
 // Integer products in double.  Snapped coordinates satisfy |X|, |Y| < 2^22
-// and pixel centres are below 2^23, so every difference is below 2^24, every
-// product or sum of two products below 2^49: all exact in a double's 53-bit
-// significand.  The results (and their conversions to float) are therefore the
+// before a view's offset (below 2^23 with it) and pixel centres are below
+// 2^23, so every difference is below 2^25, every product or sum of two
+// products below 2^51: all exact in a double's 53-bit significand.  The results (and their conversions to float) are therefore the
 // same as with 64-bit integers, at FP64 FMA rate instead of emulated 64-bit
 // integer multiplies.
 //

@@ -45,8 +45,8 @@ __device__ __forceinline__ int next_tile(int cur, int tx0, int tx1, int ty1, int
 // its box covers.  Each bin has a fixed capacity; its counter (kept at zero
 // between calls, reset by the rasterizer after reading it) gives the slot.
 __global__ void k_setup_bin(const float4 *__restrict__ pos_clip, const int32_t *__restrict__ tris,
-                            int B, int V, int T, int H, int W, int cull, int margin, int ntx, int nt,
-                            int cap, TriSetup *__restrict__ setup, int32_t *__restrict__ counts,
+                            Viewports vp, int B, int V, int T, int H, int W, int cull, int margin, int ntx,
+                            int nt, int cap, TriSetup *__restrict__ setup, int32_t *__restrict__ counts,
                             int32_t *__restrict__ bins, unsigned long long *__restrict__ status) {
     int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int cur = -1, tx0 = 0, tx1 = 0, ty1 = 0, b = 0, t = 0;
@@ -61,7 +61,8 @@ __global__ void k_setup_bin(const float4 *__restrict__ pos_clip, const int32_t *
             s.box0 = s.box1 = 1;
             s.hbox0 = s.hbox1 = 1;
         } else {
-            s = dr_setup(pos_clip + (int64_t)b * V, v0, v1, v2, H, W, cull, margin);
+            const int4 q = dr_viewport(vp, t, H, W);
+            s = dr_setup(pos_clip + (int64_t)b * V, v0, v1, v2, q.w, q.z, q.x, q.y, cull, margin);
         }
         setup[gid] = s;
         if (s.meta & 1) {
@@ -633,15 +634,15 @@ static int check_raster_args(dressi_ctx *ctx, const void *pos, const void *tris,
         return dressi_fail(ctx, DRESSI_EINVAL, "rasterize: bad dimensions");
     if (K < 1 || K > DRESSI_MAX_K) return dressi_fail(ctx, DRESSI_EINVAL, "rasterize: K must be 1..5");
     if (!(r >= 0.0f && r <= 1.0f)) return dressi_fail(ctx, DRESSI_EINVAL, "rasterize: r must be in [0,1]");
-    if (T >= (1 << 21) - 1) return dressi_fail(ctx, DRESSI_EINVAL, "rasterize: T must be < 2^21-1");
+    if (T >= 0x7fffffff) return dressi_fail(ctx, DRESSI_EINVAL, "rasterize: T must be < 2^31-1");
     if ((B * (int64_t)T > 0) && (!pos || !tris))
         return dressi_fail(ctx, DRESSI_EINVAL, "rasterize: null pos_clip or tris");
     return DRESSI_OK;
 }
 
-extern "C" int dressi_rasterize(dressi_ctx *ctx, const float *pos_clip, const int32_t *tris, int B,
-                                int V, int T, int H, int W, int K, float r, int cull,
-                                int32_t *tri_id, float *bary, float *dist, void *stream) {
+static int rasterize_impl(dressi_ctx *ctx, const float *pos_clip, const int32_t *tris, Viewports vp, int B,
+                          int V, int T, int H, int W, int K, float r, int cull, int32_t *tri_id, float *bary,
+                          float *dist, void *stream) {
     int rc = check_raster_args(ctx, pos_clip, tris, B, V, T, H, W, K, r);
     if (rc) return rc;
     if (!tri_id || !bary) return dressi_fail(ctx, DRESSI_EINVAL, "rasterize: null tri_id or bary");
@@ -666,8 +667,8 @@ extern "C" int dressi_rasterize(dressi_ctx *ctx, const float *pos_clip, const in
     int64_t ntri = (int64_t)B * T;
     if (ntri > 0)
         DR_LAUNCH("k_setup_bin", (k_setup_bin), (int)((ntri + 255) / 256), 256, 0, st,
-                  reinterpret_cast<const float4 *>(pos_clip), tris, B, V, T, H, W, cull, margin, ntx, nt,
-                  cap, setup, counts, bins, reinterpret_cast<unsigned long long *>(ctx->status));
+                  reinterpret_cast<const float4 *>(pos_clip), tris, vp, B, V, T, H, W, cull, margin, ntx,
+                  nt, cap, setup, counts, bins, reinterpret_cast<unsigned long long *>(ctx->status));
     dim3 g((unsigned)(B * nt));
     float2 *b2 = reinterpret_cast<float2 *>(bary);
     switch (K) {
@@ -680,18 +681,42 @@ extern "C" int dressi_rasterize(dressi_ctx *ctx, const float *pos_clip, const in
     return dressi_launch_check(ctx, "rasterize");
 }
 
+extern "C" int dressi_rasterize(dressi_ctx *ctx, const float *pos_clip, const int32_t *tris, int B,
+                                int V, int T, int H, int W, int K, float r, int cull,
+                                int32_t *tri_id, float *bary, float *dist, void *stream) {
+    return rasterize_impl(ctx, pos_clip, tris, Viewports{nullptr, nullptr}, B, V, T, H, W, K, r, cull, tri_id,
+                          bary, dist, stream);
+}
+
+static int check_views(dressi_ctx *ctx, const int32_t *tri_view, const void *views, int n, int T) {
+    if (n < 1) return dressi_fail(ctx, DRESSI_EINVAL, "batched: need at least one view");
+    if (T > 0 && (!tri_view || !views)) return dressi_fail(ctx, DRESSI_EINVAL, "batched: null tri_view or views");
+    return DRESSI_OK;
+}
+
+extern "C" int dressi_rasterize_batched(dressi_ctx *ctx, const float *pos_clip, const int32_t *tris,
+                                        const int32_t *tri_view, const int32_t *views, int n, int V, int T,
+                                        int H, int W, int K, int cull, int32_t *tri_id, float *bary,
+                                        void *stream) {
+    if (!ctx) return DRESSI_EINVAL;
+    int rc = check_views(ctx, tri_view, views, n, T);
+    if (rc) return rc;
+    return rasterize_impl(ctx, pos_clip, tris, Viewports{tri_view, reinterpret_cast<const int4 *>(views)}, 1, V,
+                          T, H, W, K, 0.0f, cull, tri_id, bary, nullptr, stream);
+}
+
 // ---------------------------------------------------------------------------
 // per-tile fragment lists sorted by triangle id
 // ---------------------------------------------------------------------------
 #define FS_MAXN 2048
-#define FS_SENT 0xffffffffu
+#define FS_SENT 0xffffffffffffffffull   // sort key: triangle id << 11 | local fragment
 
 __global__ void __launch_bounds__(DRESSI_TILE_PIX)
     k_fragsort(const int32_t *__restrict__ tri_id, int K, int H, int W, int ntx, int nt, int np, int T,
                int32_t *__restrict__ n_frag, int32_t *__restrict__ n_rec, uint16_t *__restrict__ frag,
                int32_t *__restrict__ rec_tri, int32_t *__restrict__ rec_start,
                int32_t *__restrict__ tri_counts) {
-    __shared__ uint32_t keys[FS_MAXN];
+    __shared__ unsigned long long keys[FS_MAXN];
     __shared__ int wsum[DRESSI_TILE_PIX / 64];
     const int bt = blockIdx.x;
     const int b = bt / nt, tile = bt - b * nt;
@@ -706,7 +731,8 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX)
         for (int k = 0; k < K; k++) {
             int t = tri_id[(((int64_t)b * K + k) * H + y) * W + x];
             if (t >= 0) {
-                keys[k * DRESSI_TILE_PIX + p] = ((uint32_t)t << 11) | (uint32_t)(k * DRESSI_TILE_PIX + p);
+                keys[k * DRESSI_TILE_PIX + p] =
+                    ((unsigned long long)t << 11) | (unsigned long long)(k * DRESSI_TILE_PIX + p);
                 any = 1;
             }
         }
@@ -725,7 +751,7 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX)
                 int lo = 2 * i - (i & (stride - 1));
                 int hi = lo + stride;
                 bool asc = (lo & size) == 0;
-                uint32_t a = keys[lo], c = keys[hi];
+                unsigned long long a = keys[lo], c = keys[hi];
                 if ((a > c) == asc) {
                     keys[lo] = c;
                     keys[hi] = a;
@@ -739,7 +765,7 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX)
     const int i0 = p * per;
     int heads = 0, valid = 0;
     for (int j = 0; j < per; j++) {
-        uint32_t kv = keys[i0 + j];
+        unsigned long long kv = keys[i0 + j];
         if (kv == FS_SENT) break;
         valid++;
         if (i0 + j == 0 || (keys[i0 + j - 1] >> 11) != (kv >> 11)) heads++;
@@ -766,7 +792,7 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX)
     int r = rbase;
     for (int j = 0; j < per; j++) {
         int i = i0 + j;
-        uint32_t kv = keys[i];
+        unsigned long long kv = keys[i];
         if (kv == FS_SENT) break;
         frag[base + i] = (uint16_t)(kv & 2047u);
         if (i == 0 || (keys[i - 1] >> 11) != (kv >> 11)) {
@@ -1001,8 +1027,8 @@ __device__ __forceinline__ void rast_frag_grad(const TriSetup &s, int x, int y, 
 }
 
 __global__ void __launch_bounds__(DRESSI_TILE_PIX)
-    k_rast_bwd_tile(const float4 *__restrict__ pos_clip, const int32_t *__restrict__ tris, int V, int T,
-                    int H, int W, int K, int cull, int margin, const int32_t *__restrict__ tri_id,
+    k_rast_bwd_tile(const float4 *__restrict__ pos_clip, const int32_t *__restrict__ tris, Viewports vp, int V,
+                    int T, int H, int W, int K, int cull, int margin, const int32_t *__restrict__ tri_id,
                     FragLists fl, int ntx, int nt, const float2 *__restrict__ grad_bary,
                     const float *__restrict__ grad_dist, float *__restrict__ partial) {
     extern __shared__ float vals[];   // [K*256][9]
@@ -1021,7 +1047,8 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX)
             int t = tri_id[o];
             if (t < 0 || t >= T) continue;
             const int32_t *tv = tris + 3 * (int64_t)t;
-            TriSetup s = dr_setup(pc, tv[0], tv[1], tv[2], H, W, cull, margin);
+            const int4 q = dr_viewport(vp, t, H, W);
+            TriSetup s = dr_setup(pc, tv[0], tv[1], tv[2], q.w, q.z, q.x, q.y, cull, margin);
             float *dst = vals + (k * DRESSI_TILE_PIX + p) * 9;
             if (!(s.meta & 1)) {
 #pragma unroll
@@ -1058,7 +1085,7 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX)
 // per (view, triangle): sum its tile records, map screen -> clip
 // (x_s = (x/w + 1) W/2, y_s = (1 - y/w) H/2)
 __global__ void k_rast_bwd_sum(const float4 *__restrict__ pos_clip, const int32_t *__restrict__ tris,
-                               int B, int V, int T, int H, int W, int K, TriTiles tt,
+                               Viewports vp, int B, int V, int T, int H, int W, int K, TriTiles tt,
                                const float *__restrict__ partial, float *__restrict__ corner_grad) {
     int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (gid >= (int64_t)B * T) return;
@@ -1074,7 +1101,8 @@ __global__ void k_rast_bwd_sum(const float4 *__restrict__ pos_clip, const int32_
     }
     float *cg = corner_grad + gid * 9;
     const int32_t *tv = tris + 3 * (int64_t)t;
-    const double hw = 0.5 * (double)W, hh = 0.5 * (double)H;
+    const int4 q = dr_viewport(vp, t, H, W);
+    const double hw = 0.5 * (double)q.z, hh = 0.5 * (double)q.w;
 #pragma unroll
     for (int i = 0; i < 3; i++) {
         int v = tv[i];
@@ -1114,11 +1142,11 @@ static size_t partial_floats(int B, int K, int H, int W, int per) {
     return (size_t)B * tiles_x(W) * tiles_y(H) * DRESSI_TILE_PIX * K * per;
 }
 
-extern "C" int dressi_rasterize_bwd(dressi_ctx *ctx, const float *pos_clip, const int32_t *tris,
-                                    int B, int V, int T, int H, int W, int K, float r, int cull,
-                                    const int32_t *tri_id, const float *grad_bary,
-                                    const float *grad_dist, const void *frag_index,
-                                    const int32_t *adj, float *grad_pos_clip, void *stream) {
+static int rasterize_bwd_impl(dressi_ctx *ctx, const float *pos_clip, const int32_t *tris, Viewports vp,
+                              int B, int V, int T, int H, int W, int K, float r, int cull,
+                              const int32_t *tri_id, const float *grad_bary, const float *grad_dist,
+                              const void *frag_index, const int32_t *adj, float *grad_pos_clip,
+                              void *stream) {
     int rc = check_raster_args(ctx, pos_clip, tris, B, V, T, H, W, K, r);
     if (rc) return rc;
     if (!tri_id || !grad_bary || (!grad_pos_clip && B * (int64_t)V > 0))
@@ -1162,15 +1190,37 @@ extern "C" int dressi_rasterize_bwd(dressi_ctx *ctx, const float *pos_clip, cons
     if ((int64_t)B * nt > 0)
         DR_LAUNCH("k_rast_bwd_tile", (k_rast_bwd_tile), B * nt, DRESSI_TILE_PIX,
                   sizeof(float) * 9 * DRESSI_TILE_PIX * K, st, reinterpret_cast<const float4 *>(pos_clip), tris,
-                  V, T, H, W, K, cull, margin, tri_id, fl, ntx, nt, reinterpret_cast<const float2 *>(grad_bary),
-                  grad_dist, part);
+                  vp, V, T, H, W, K, cull, margin, tri_id, fl, ntx, nt,
+                  reinterpret_cast<const float2 *>(grad_bary), grad_dist, part);
     if (ntri > 0)
         DR_LAUNCH("k_rast_bwd_sum", (k_rast_bwd_sum), (int)((ntri + 255) / 256), 256, 0, st,
-                  reinterpret_cast<const float4 *>(pos_clip), tris, B, V, T, H, W, K, tt, part, cg);
+                  reinterpret_cast<const float4 *>(pos_clip), tris, vp, B, V, T, H, W, K, tt, part, cg);
     int64_t nv = (int64_t)B * V;
     DR_LAUNCH("k_vertex_gather_pos", (k_vertex_gather_pos), (int)((nv + 255) / 256), 256, 0, st, cg, A, B,
               V, T, reinterpret_cast<float4 *>(grad_pos_clip));
     return dressi_launch_check(ctx, "rasterize_bwd");
+}
+
+extern "C" int dressi_rasterize_bwd(dressi_ctx *ctx, const float *pos_clip, const int32_t *tris,
+                                    int B, int V, int T, int H, int W, int K, float r, int cull,
+                                    const int32_t *tri_id, const float *grad_bary,
+                                    const float *grad_dist, const void *frag_index,
+                                    const int32_t *adj, float *grad_pos_clip, void *stream) {
+    return rasterize_bwd_impl(ctx, pos_clip, tris, Viewports{nullptr, nullptr}, B, V, T, H, W, K, r, cull, tri_id,
+                              grad_bary, grad_dist, frag_index, adj, grad_pos_clip, stream);
+}
+
+extern "C" int dressi_rasterize_batched_bwd(dressi_ctx *ctx, const float *pos_clip, const int32_t *tris,
+                                            const int32_t *tri_view, const int32_t *views, int n, int V, int T,
+                                            int H, int W, int K, int cull, const int32_t *tri_id,
+                                            const float *grad_bary, const void *frag_index, const int32_t *adj,
+                                            float *grad_pos_clip, void *stream) {
+    if (!ctx) return DRESSI_EINVAL;
+    int rc = check_views(ctx, tri_view, views, n, T);
+    if (rc) return rc;
+    return rasterize_bwd_impl(ctx, pos_clip, tris, Viewports{tri_view, reinterpret_cast<const int4 *>(views)}, 1,
+                              V, T, H, W, K, 0.0f, cull, tri_id, grad_bary, nullptr, frag_index, adj,
+                              grad_pos_clip, stream);
 }
 
 // ---------------------------------------------------------------------------

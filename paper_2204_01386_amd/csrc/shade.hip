@@ -10,12 +10,13 @@
 // ---------------------------------------------------------------------------
 // transform
 // ---------------------------------------------------------------------------
-__global__ void k_transform(const float *__restrict__ pos, const float *__restrict__ mvp, int B, int V,
-                            float4 *__restrict__ out) {
+// With vert_view (uneven batches, B = 1), vertex v uses the matrix of its own view.
+__global__ void k_transform(const float *__restrict__ pos, const float *__restrict__ mvp,
+                            const int32_t *__restrict__ vert_view, int B, int V, float4 *__restrict__ out) {
     int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (gid >= (int64_t)B * V) return;
     int b = (int)(gid / V), v = (int)(gid - (int64_t)b * V);
-    const float *M = mvp + 16 * b;
+    const float *M = mvp + 16 * (int64_t)(vert_view ? vert_view[v] : b);
     float x = pos[3 * (int64_t)v], y = pos[3 * (int64_t)v + 1], z = pos[3 * (int64_t)v + 2];
     float4 o;
     o.x = M[0] * x + M[1] * y + M[2] * z + M[3];
@@ -25,13 +26,13 @@ __global__ void k_transform(const float *__restrict__ pos, const float *__restri
     out[gid] = o;
 }
 
-__global__ void k_transform_bwd(const float *__restrict__ mvp, int B, int V,
-                                const float4 *__restrict__ g, float *__restrict__ grad_pos) {
+__global__ void k_transform_bwd(const float *__restrict__ mvp, const int32_t *__restrict__ vert_view, int B,
+                                int V, const float4 *__restrict__ g, float *__restrict__ grad_pos) {
     int v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= V) return;
     float gx = 0.0f, gy = 0.0f, gz = 0.0f;
     for (int b = 0; b < B; b++) {
-        const float *M = mvp + 16 * b;
+        const float *M = mvp + 16 * (int64_t)(vert_view ? vert_view[v] : b);
         float4 q = g[(int64_t)b * V + v];
         gx += M[0] * q.x + M[4] * q.y + M[8] * q.z + M[12] * q.w;
         gy += M[1] * q.x + M[5] * q.y + M[9] * q.z + M[13] * q.w;
@@ -49,9 +50,33 @@ extern "C" int dressi_transform(dressi_ctx *ctx, const float *pos, const float *
     if ((int64_t)B * V == 0) return DRESSI_OK;
     if (!pos || !mvp || !pos_clip) return dressi_fail(ctx, DRESSI_EINVAL, "transform: null pointer");
     int64_t n = (int64_t)B * V;
-    DR_LAUNCH("k_transform", (k_transform), (int)((n + 255) / 256), 256, 0, (hipStream_t)stream, 
-        pos, mvp, B, V, reinterpret_cast<float4 *>(pos_clip));
+    DR_LAUNCH("k_transform", (k_transform), (int)((n + 255) / 256), 256, 0, (hipStream_t)stream, pos, mvp,
+              nullptr, B, V, reinterpret_cast<float4 *>(pos_clip));
     return dressi_launch_check(ctx, "transform");
+}
+
+extern "C" int dressi_transform_batched(dressi_ctx *ctx, const float *pos, const int32_t *vert_view,
+                                        const float *mvp, int V, float *pos_clip, void *stream) {
+    if (!ctx) return DRESSI_EINVAL;
+    if (V < 0) return dressi_fail(ctx, DRESSI_EINVAL, "transform_batched: bad dimensions");
+    if (V == 0) return DRESSI_OK;
+    if (!pos || !vert_view || !mvp || !pos_clip)
+        return dressi_fail(ctx, DRESSI_EINVAL, "transform_batched: null pointer");
+    DR_LAUNCH("k_transform", (k_transform), (V + 255) / 256, 256, 0, (hipStream_t)stream, pos, mvp, vert_view, 1,
+              V, reinterpret_cast<float4 *>(pos_clip));
+    return dressi_launch_check(ctx, "transform_batched");
+}
+
+extern "C" int dressi_transform_batched_bwd(dressi_ctx *ctx, const float *mvp, const int32_t *vert_view, int V,
+                                            const float *grad_clip, float *grad_pos, void *stream) {
+    if (!ctx) return DRESSI_EINVAL;
+    if (V < 0) return dressi_fail(ctx, DRESSI_EINVAL, "transform_batched_bwd: bad dimensions");
+    if (V == 0) return DRESSI_OK;
+    if (!mvp || !vert_view || !grad_clip || !grad_pos)
+        return dressi_fail(ctx, DRESSI_EINVAL, "transform_batched_bwd: null pointer");
+    DR_LAUNCH("k_transform_bwd", (k_transform_bwd), (V + 255) / 256, 256, 0, (hipStream_t)stream, mvp, vert_view,
+              1, V, reinterpret_cast<const float4 *>(grad_clip), grad_pos);
+    return dressi_launch_check(ctx, "transform_batched_bwd");
 }
 
 extern "C" int dressi_transform_bwd(dressi_ctx *ctx, const float *mvp, int B, int V,
@@ -61,8 +86,8 @@ extern "C" int dressi_transform_bwd(dressi_ctx *ctx, const float *mvp, int B, in
     if (V == 0) return DRESSI_OK;
     if (!grad_pos || (B > 0 && (!mvp || !grad_clip)))
         return dressi_fail(ctx, DRESSI_EINVAL, "transform_bwd: null pointer");
-    DR_LAUNCH("k_transform_bwd", (k_transform_bwd), (V + 255) / 256, 256, 0, (hipStream_t)stream, 
-        mvp, B, V, reinterpret_cast<const float4 *>(grad_clip), grad_pos);
+    DR_LAUNCH("k_transform_bwd", (k_transform_bwd), (V + 255) / 256, 256, 0, (hipStream_t)stream, mvp, nullptr,
+              B, V, reinterpret_cast<const float4 *>(grad_clip), grad_pos);
     return dressi_launch_check(ctx, "transform_bwd");
 }
 
@@ -282,9 +307,9 @@ __global__ void k_shade(int mode, dressi_frag_in in, const float *__restrict__ e
         if (dir) { dir[3 * i] = 0.0f; dir[3 * i + 1] = 0.0f; dir[3 * i + 2] = 0.0f; }
         return;
     }
-    int b = (int)(i / Npv);
+    const int64_t e = in.tri_eye ? (int64_t)in.tri_eye[tri_id[i]] : i / Npv;
     ShadeState s;
-    shade_forward(mode, in, eye + 3 * b, i, mode != DRESSI_SHADE_LAMBERT || dir != nullptr, s);
+    shade_forward(mode, in, eye + 3 * e, i, mode != DRESSI_SHADE_LAMBERT || dir != nullptr, s);
     if (dir) {
         float3 d = (2.0f * dot3(s.np, s.vh)) * s.np - s.vh;
         dir[3 * i] = d.x; dir[3 * i + 1] = d.y; dir[3 * i + 2] = d.z;
@@ -323,10 +348,10 @@ __global__ void k_shade_bwd(int mode, dressi_frag_in in, const float *__restrict
         }
         return;
     }
-    int b = (int)(i / Npv);
+    const int64_t e = in.tri_eye ? (int64_t)in.tri_eye[tri_id[i]] : i / Npv;
     bool need_geo = gr.normal || gr.pos || gr.tangent || gr.nmap;
     ShadeState s;
-    shade_forward(mode, in, eye + 3 * b, i, mode != DRESSI_SHADE_LAMBERT || grad_dir != nullptr, s);
+    shade_forward(mode, in, eye + 3 * e, i, mode != DRESSI_SHADE_LAMBERT || grad_dir != nullptr, s);
     float3 g = grad_color ? ld3(grad_color + 3 * i) : Z;
     float gsum = g.x + g.y + g.z;
     if (gr.albedo) {
@@ -439,9 +464,9 @@ extern "C" int dressi_shade_bwd(dressi_ctx *ctx, int mode, const dressi_frag_in 
 
 __global__ void __launch_bounds__(LOSS_BS)
     k_loss_l2(const float *__restrict__ color, const float *__restrict__ sil,
-              const float *__restrict__ target, int64_t n, float inv, float *__restrict__ grad_color,
-              float *__restrict__ grad_sil, float *__restrict__ partial, int32_t *__restrict__ done,
-              float *__restrict__ loss) {
+              const float *__restrict__ target, const float *__restrict__ weight, int64_t n, float inv,
+              float *__restrict__ grad_color, float *__restrict__ grad_sil, float *__restrict__ partial,
+              int32_t *__restrict__ done, float *__restrict__ loss) {
     __shared__ float red[LOSS_BS];
     __shared__ int last;
     float acc = 0.0f;
@@ -449,13 +474,16 @@ __global__ void __launch_bounds__(LOSS_BS)
         float4 t = reinterpret_cast<const float4 *>(target)[i];
         float d0 = color[3 * i] - t.x, d1 = color[3 * i + 1] - t.y, d2 = color[3 * i + 2] - t.z;
         float d3 = sil[i] - t.w;
-        acc += d0 * d0 + d1 * d1 + d2 * d2 + d3 * d3;
+        const float sq = d0 * d0 + d1 * d1 + d2 * d2 + d3 * d3;
+        // per-pixel weight (uneven batches: 1 / (4 H_i W_i) of the pixel's view), else uniform
+        const float w = weight ? weight[i] : inv;
+        acc += weight ? w * sq : sq;
         if (grad_color) {
-            grad_color[3 * i] = 2.0f * inv * d0;
-            grad_color[3 * i + 1] = 2.0f * inv * d1;
-            grad_color[3 * i + 2] = 2.0f * inv * d2;
+            grad_color[3 * i] = 2.0f * w * d0;
+            grad_color[3 * i + 1] = 2.0f * w * d1;
+            grad_color[3 * i + 2] = 2.0f * w * d2;
         }
-        if (grad_sil) grad_sil[i] = 2.0f * inv * d3;
+        if (grad_sil) grad_sil[i] = 2.0f * w * d3;
     }
     red[threadIdx.x] = acc;
     __syncthreads();
@@ -481,14 +509,14 @@ __global__ void __launch_bounds__(LOSS_BS)
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        loss[0] = red[0] * inv;
+        loss[0] = weight ? red[0] : red[0] * inv;
         *done = 0;   // leave the counter at zero
     }
 }
 
 extern "C" int dressi_loss_l2(dressi_ctx *ctx, const float *color, const float *sil, const float *target,
-                              int B, int H, int W, float *loss, float *grad_color, float *grad_sil,
-                              void *stream) {
+                              const float *weight, int B, int H, int W, float *loss, float *grad_color,
+                              float *grad_sil, void *stream) {
     if (!ctx) return DRESSI_EINVAL;
     if (B < 0 || H < 0 || W < 0) return dressi_fail(ctx, DRESSI_EINVAL, "loss_l2: bad dimensions");
     int64_t n = (int64_t)B * H * W;
@@ -506,7 +534,7 @@ extern "C" int dressi_loss_l2(dressi_ctx *ctx, const float *color, const float *
     if (rc) return rc;
     float *partial = at<float>(ctx->scratch, o_p);
     float inv = 1.0f / (4.0f * (float)(n > 0 ? n : 1));
-    DR_LAUNCH("k_loss_l2", (k_loss_l2), nb, LOSS_BS, 0, st, color, sil, target, n, inv, grad_color, grad_sil,
-              partial, ctx->counters, loss);
+    DR_LAUNCH("k_loss_l2", (k_loss_l2), nb, LOSS_BS, 0, st, color, sil, target, weight, n, inv, grad_color,
+              grad_sil, partial, ctx->counters, loss);
     return dressi_launch_check(ctx, "loss_l2");
 }

@@ -73,7 +73,18 @@ __device__ __forceinline__ int cube_face(float x, float y, float z, float &u, fl
     return f;
 }
 
-__device__ __forceinline__ Taps make_taps(const dressi_tex_desc &td, const float *q) {
+// Number of 2-D faces or layers of a texture.
+__host__ __device__ __forceinline__ int tex_faces(const dressi_tex_desc &td) {
+    return td.kind == DRESSI_TEX_CUBE ? 6 : (td.kind == DRESSI_TEX_2D_ARRAY ? td.layers : 1);
+}
+
+// Layer of fragment i of a texture array (its triangle's layer), 0 otherwise.
+__device__ __forceinline__ int tex_layer(const dressi_tex_desc &td, const int32_t *__restrict__ tri_id,
+                                         int64_t i) {
+    return td.kind == DRESSI_TEX_2D_ARRAY ? td.tri_layer[tri_id[i]] : 0;
+}
+
+__device__ __forceinline__ Taps make_taps(const dressi_tex_desc &td, const float *q, int layer = 0) {
     Taps t;
     t.ok = 0;
     float u, v;
@@ -88,6 +99,7 @@ __device__ __forceinline__ Taps make_taps(const dressi_tex_desc &td, const float
     } else {
         u = q[0];
         v = q[1];
+        t.face = layer;
     }
     taps1d(u, td.Wt, wu, t.x0, t.x1, t.fx);
     taps1d(v, td.Ht, wv, t.y0, t.y1, t.fy);
@@ -145,7 +157,7 @@ __global__ void __launch_bounds__(256)
     float r[TEX_NC(CT)];
     Taps t;
     t.ok = 0;
-    if (!tri_id || tri_id[i] >= 0) t = make_taps(td, coord + i * cd);
+    if (!tri_id || tri_id[i] >= 0) t = make_taps(td, coord + i * cd, tex_layer(td, tri_id, i));
     if (!t.ok) {
 #pragma unroll
         for (int c = 0; c < TEX_NC(CT); c++) r[c] = 0.0f;
@@ -182,7 +194,7 @@ __global__ void __launch_bounds__(256)
     Taps t;
     t.ok = 0;
     bool covered = !tri_id || tri_id[i] >= 0;
-    if (covered) t = make_taps(td, q);
+    if (covered) t = make_taps(td, q, tex_layer(td, tri_id, i));
     if (inv && covered && t.ok) {
         int s = (int)(i / npix);
         int pix = (int)(i - (int64_t)s * npix);
@@ -196,7 +208,7 @@ __global__ void __launch_bounds__(256)
             cx = cell1d(q[0], td.Wt, td.wrap_u);
             cy = cell1d(q[1], td.Ht, td.wrap_v);
         }
-        int64_t cells = (int64_t)(cube ? 6 : 1) * td.Ht * td.Wt;
+        int64_t cells = (int64_t)tex_faces(td) * td.Ht * td.Wt;
         atomicMax(&inv[(int64_t)s * cells + ((int64_t)t.face * td.Ht + cy) * td.Wt + cx], pix);
     }
     if (!grad_coord) return;
@@ -262,9 +274,9 @@ __global__ void __launch_bounds__(256)
 // range is split over grid.z and each part writes its own partial sum.
 template <int CT>
 __global__ void __launch_bounds__(IV_T * IV_T)
-    k_invuv_gather(dressi_tex_desc td, const float *__restrict__ coord, int64_t npix, int S, int nsplit,
-                   const int32_t *__restrict__ inv, const float *__restrict__ grad_out,
-                   float *__restrict__ out) {
+    k_invuv_gather(dressi_tex_desc td, const float *__restrict__ coord, const int32_t *__restrict__ tri_id,
+                   int64_t npix, int S, int nsplit, const int32_t *__restrict__ inv,
+                   const float *__restrict__ grad_out, float *__restrict__ out) {
     // per halo cell of each slice of the group: the winner pixel (-1: none or
     // another cube face), its four tap coordinates and bilinear fractions
     __shared__ int cpix[DRESSI_IV_SG][IV_H * IV_H];
@@ -272,7 +284,7 @@ __global__ void __launch_bounds__(IV_T * IV_T)
     __shared__ float2 cfr[DRESSI_IV_SG][IV_H * IV_H];  // fx, fy
     const int Ht = td.Ht, Wt = td.Wt, Ct = CT > 0 ? CT : td.Ct;
     const bool cube = td.kind == DRESSI_TEX_CUBE;
-    const int F = cube ? 6 : 1;
+    const int F = tex_faces(td);
     const int wu = cube ? DRESSI_WRAP_CLAMP : td.wrap_u;
     const int wv = cube ? DRESSI_WRAP_CLAMP : td.wrap_v;
     const int cd = cube ? 3 : 2;
@@ -326,7 +338,8 @@ __global__ void __launch_bounds__(IV_T * IV_T)
                 int2 tp = make_int2(0, 0);
                 float2 fr = make_float2(0.0f, 0.0f);
                 if (i >= 0) {
-                    const Taps t = make_taps(td, coord + ((int64_t)(g0 + q) * npix + i) * cd);
+                    const int64_t o = (int64_t)(g0 + q) * npix + i;
+                    const Taps t = make_taps(td, coord + o * cd, tex_layer(td, tri_id, o));
                     if (!t.ok || t.face != f) {
                         i = -1;
                     } else {
@@ -394,13 +407,15 @@ static int check_tex(dressi_ctx *ctx, const void *tex, const dressi_tex_desc *td
                      const void *tid, int S, int H, int W) {
     if (!ctx) return DRESSI_EINVAL;
     if (!td) return dressi_fail(ctx, DRESSI_EINVAL, "texture: null descriptor");
-    if (td->kind != DRESSI_TEX_2D && td->kind != DRESSI_TEX_CUBE)
+    if (td->kind != DRESSI_TEX_2D && td->kind != DRESSI_TEX_CUBE && td->kind != DRESSI_TEX_2D_ARRAY)
         return dressi_fail(ctx, DRESSI_EINVAL, "texture: bad kind");
+    if (td->kind == DRESSI_TEX_2D_ARRAY && (td->layers < 1 || !td->tri_layer || !tid))
+        return dressi_fail(ctx, DRESSI_EINVAL, "texture: an array needs layers >= 1, tri_layer and tri_id");
     if (td->Ht < 1 || td->Wt < 1 || td->Ct < 1 || td->Ct > 16 || td->Ht > 32767 || td->Wt > 32767)
         return dressi_fail(ctx, DRESSI_EINVAL, "texture: bad texture shape (Ht, Wt 1..32767, Ct 1..16)");
     if (td->kind == DRESSI_TEX_CUBE && td->Ht != td->Wt)
         return dressi_fail(ctx, DRESSI_EINVAL, "texture: cube faces must be square");
-    if (td->kind == DRESSI_TEX_2D) {
+    if (td->kind != DRESSI_TEX_CUBE) {
         for (int w : {td->wrap_u, td->wrap_v})
             if (w != DRESSI_WRAP_REPEAT && w != DRESSI_WRAP_CLAMP)
                 return dressi_fail(ctx, DRESSI_EINVAL, "texture: bad wrap mode");
@@ -441,13 +456,13 @@ extern "C" int dressi_texture_bwd(dressi_ctx *ctx, const float *tex, const dress
     if (n > 0 && !grad_out) return dressi_fail(ctx, DRESSI_EINVAL, "texture_bwd: null grad_out");
     if (grad_tex && !tri_id)
         return dressi_fail(ctx, DRESSI_EINVAL, "texture_bwd: the texture gradient needs tri_id");
-    if (grad_tex && td->kind == DRESSI_TEX_2D &&
+    if (grad_tex && td->kind != DRESSI_TEX_CUBE &&
         ((td->wrap_u == DRESSI_WRAP_REPEAT && td->Wt < 3) || (td->wrap_v == DRESSI_WRAP_REPEAT && td->Ht < 3)))
         return dressi_fail(ctx, DRESSI_EINVAL, "texture_bwd: repeat wrap needs at least 3 texels");
     hipStream_t st = (hipStream_t)stream;
     int32_t *inv = nullptr;
     float *part = nullptr;
-    int64_t cells = (int64_t)(td->kind == DRESSI_TEX_CUBE ? 6 : 1) * td->Ht * td->Wt;
+    int64_t cells = (int64_t)tex_faces(*td) * td->Ht * td->Wt;
     if (grad_tex) {
         Carver c;
         size_t o_inv = c.take(sizeof(int32_t) * (size_t)cells * (S > 0 ? S : 1));
@@ -480,19 +495,19 @@ extern "C" int dressi_texture_bwd(dressi_ctx *ctx, const float *tex, const dress
         float *dst = grad_tex;
         if (nsplit > 1) dst = part;
         dim3 g((unsigned)((td->Wt + IV_T - 1) / IV_T), (unsigned)((td->Ht + IV_T - 1) / IV_T),
-               (unsigned)((td->kind == DRESSI_TEX_CUBE ? 6 : 1) * nsplit));
+               (unsigned)(tex_faces(*td) * nsplit));
         const int ct = aligned16(grad_out, dst) ? td->Ct : 0;
         if (ct == 4)
-            DR_LAUNCH("k_invuv_gather", (k_invuv_gather<4>), g, IV_T * IV_T, 0, st, *td, coord, npix, S, nsplit,
+            DR_LAUNCH("k_invuv_gather", (k_invuv_gather<4>), g, IV_T * IV_T, 0, st, *td, coord, tri_id, npix, S, nsplit,
                       inv, grad_out, dst);
         else if (ct == 3)
-            DR_LAUNCH("k_invuv_gather", (k_invuv_gather<3>), g, IV_T * IV_T, 0, st, *td, coord, npix, S, nsplit,
+            DR_LAUNCH("k_invuv_gather", (k_invuv_gather<3>), g, IV_T * IV_T, 0, st, *td, coord, tri_id, npix, S, nsplit,
                       inv, grad_out, dst);
         else if (ct == 8)
-            DR_LAUNCH("k_invuv_gather", (k_invuv_gather<8>), g, IV_T * IV_T, 0, st, *td, coord, npix, S, nsplit,
+            DR_LAUNCH("k_invuv_gather", (k_invuv_gather<8>), g, IV_T * IV_T, 0, st, *td, coord, tri_id, npix, S, nsplit,
                       inv, grad_out, dst);
         else
-            DR_LAUNCH("k_invuv_gather", (k_invuv_gather<0>), g, IV_T * IV_T, 0, st, *td, coord, npix, S, nsplit,
+            DR_LAUNCH("k_invuv_gather", (k_invuv_gather<0>), g, IV_T * IV_T, 0, st, *td, coord, tri_id, npix, S, nsplit,
                       inv, grad_out, dst);
         if (nsplit > 1) {
             int64_t ne = cells * td->Ct;

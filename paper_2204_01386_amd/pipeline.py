@@ -224,7 +224,7 @@ class Step:
 
     def loss_and_grad(self):
         ck = self._chk
-        ck(_lib.dressi_loss_l2(self.ctx.handle, _p(self.color), _p(self.sil), _p(self.target), self.B,
+        ck(_lib.dressi_loss_l2(self.ctx.handle, _p(self.color), _p(self.sil), _p(self.target), None, self.B,
                                self.H, self.W, _p(self.loss), _p(self.g_color), _p(self.g_sil),
                                self._s()), "loss")
 
@@ -316,5 +316,230 @@ def make_target(scene: Scene, device="cuda", views=None) -> Step:
     if scene.target_tex is not None:
         params["tex"] = f32(pack_textures(scene.target_tex, scene.nmap))
     st = Step(scene, device, views=views, params=params)
+    st.forward()
+    return st
+
+
+# ---------------------------------------------------------------------------
+# uneven batches
+# ---------------------------------------------------------------------------
+def pack_views(sizes, width=None):
+    """Shelf packing of views (W_i, H_i) into one image: views sorted by
+    height (then width, then index) fill rows left to right.  Returns the
+    (x0, y0) of every view and the image size (Wc, Hc)."""
+    n = len(sizes)
+    area = sum(w * h for w, h in sizes)
+    if width is None:
+        width = max(max(w for w, _ in sizes), int(math.ceil(math.sqrt(1.25 * area) / 256.0)) * 256)
+    order = sorted(range(n), key=lambda i: (-sizes[i][1], -sizes[i][0], i))
+    x = y = shelf = 0
+    at = [None] * n
+    for i in order:
+        w, h = sizes[i]
+        if x + w > width:
+            y += shelf
+            x = shelf = 0
+        at[i] = (x, y)
+        x += w
+        shelf = max(shelf, h)
+    return at, (width, y + shelf)
+
+
+class BatchStep:
+    """Preallocated fwd+bwd of an uneven batch of standalone scenes (K=1,
+    Phong, one 2-D texture each): the meshes are concatenated, every view is
+    drawn into its own rectangle of one image and every stage is one launch
+    for the whole batch.  The loss is the sum of the per-view L2 means."""
+
+    def __init__(self, scenes_list, device="cuda", target: "BatchStep | None" = None,
+                 params: list | None = None):
+        dev = torch.device(device)
+        self.dev = dev
+        self.scenes = scenes_list
+        n = self.n = len(scenes_list)
+        for s in scenes_list:
+            assert s.K == 1 and s.r == 0 and s.shading == "phong" and s.nmap is None, "K=1 Phong scenes only"
+            assert s.tex.shape == scenes_list[0].tex.shape, "one texture size for the batch"
+        f32 = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(dev)
+        i32 = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.int32)).to(dev)
+        sizes = [(s.W, s.H) for s in scenes_list]
+        at, (Wc, Hc) = pack_views(sizes)
+        self.at, self.W, self.H = at, Wc, Hc
+        self.views_np = np.array([(at[i][0], at[i][1], sizes[i][0], sizes[i][1]) for i in range(n)], np.int32)
+        V = [s.pos.shape[0] for s in scenes_list]
+        T = [s.tris.shape[0] for s in scenes_list]
+        Vu = [s.uv.shape[0] for s in scenes_list]
+        self.vbase = np.concatenate([[0], np.cumsum(V)]).astype(np.int64)
+        self.tbase = np.concatenate([[0], np.cumsum(T)]).astype(np.int64)
+        ubase = np.concatenate([[0], np.cumsum(Vu)]).astype(np.int64)
+        self.V, self.T = int(self.vbase[-1]), int(self.tbase[-1])
+        p = params or [{} for _ in range(n)]
+        pos = [p[i].get("pos", s.pos) for i, s in enumerate(scenes_list)]
+        tex = [p[i].get("tex", s.tex) for i, s in enumerate(scenes_list)]
+        self.pos = f32(np.concatenate(pos))
+        self.tris = i32(np.concatenate([s.tris + self.vbase[i] for i, s in enumerate(scenes_list)]))
+        self.uv = f32(np.concatenate([s.uv for s in scenes_list]))
+        self.uv_tris = i32(np.concatenate([s.uv_tris + ubase[i] for i, s in enumerate(scenes_list)]))
+        self.vert_view = i32(np.repeat(np.arange(n), V))
+        self.tri_view = i32(np.repeat(np.arange(n), T))
+        self.views = i32(self.views_np)
+        self.mvp = f32(np.stack([s.mvp[0] for s in scenes_list]))
+        self.eye = f32(np.stack([s.eyes[0] for s in scenes_list]))
+        self.tex = f32(np.stack(tex))
+        wu, wv = scenes_list[0].extra.get("wrap", (Bd.WRAP_REPEAT, Bd.WRAP_CLAMP))
+        Ht, Wt, Ct = self.tex.shape[1:]
+        self.Ct = Ct
+        self.desc = Bd.TexDesc(Bd.TEX_2D_ARRAY, Ht, Wt, Ct, wu, wv, n, self.tri_view.data_ptr())
+        wgt = np.zeros((Hc, Wc), np.float32)
+        for i, (x0, y0, w, h) in enumerate(self.views_np):
+            wgt[y0:y0 + h, x0:x0 + w] = np.float32(1.0) / np.float32(4.0 * float(w * h))
+        self.weight = f32(wgt)
+        e = lambda *s, dt=torch.float32: torch.empty(s, dtype=dt, device=dev)
+        H, W = Hc, Wc
+        self.Cv = 6
+        self.vattr = e(self.V, 6)
+        self.pos_clip = e(self.V, 4)
+        self.tri_id = e(1, 1, H, W, dt=torch.int32)
+        self.bary = e(1, 1, H, W, 2)
+        self.gbuf = e(1, 1, H, W, 6)
+        self.uvbuf = e(1, 1, H, W, 2)
+        self.samp = e(1, 1, H, W, Ct)
+        self.layer_color = e(1, 1, H, W, 3)
+        self.color = e(1, H, W, 3)
+        self.sil = e(1, H, W)
+        self.E = e(1, H, W, dt=torch.uint8)
+        self.loss = e(1)
+        self.target = e(1, H, W, 4) if target is None else target.rgba()
+        self.g_color = e(1, H, W, 3)
+        self.g_sil = e(1, H, W)
+        self.g_layer = e(1, 1, H, W, 3)
+        self.g_gbuf = e(1, 1, H, W, 6)
+        self.g_samp = e(1, 1, H, W, Ct)
+        self.g_tex = torch.empty_like(self.tex)
+        self.g_uvbuf = e(1, 1, H, W, 2)
+        self.g_bary_uv = e(1, 1, H, W, 2)
+        self.g_bary = e(1, 1, H, W, 2)
+        self.g_vattr = e(self.V, 6)
+        self.g_clip = e(self.V, 4)
+        self.g_pos_t = e(self.V, 3)
+        self.g_pos = e(self.V, 3)
+        self.ctx = Bd.context(dev.index)
+        self.adj = Bd.dressi_adjacency(self.tris, self.V)
+        self.uv_adj = Bd.dressi_adjacency(self.uv_tris, self.uv.shape[0])
+        nbytes = int(_lib.dressi_fragment_index_bytes(1, 1, H, W, self.T))
+        self.frag_index = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        fi = Bd.FragIn()
+        fi.normal, fi.normal_stride = _cp(self.gbuf, 0), 6
+        fi.pos, fi.pos_stride = _cp(self.gbuf, 3), 6
+        fi.albedo, fi.albedo_stride, fi.albedo_channels = _cp(self.samp, 0), Ct, 4
+        fi.tri_eye = C.c_void_p(self.tri_view.data_ptr())
+        self._fin = fi
+        self._calibrate_bins()
+
+    def _s(self):
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+    def _chk(self, rc, what):
+        if rc != 0:
+            self.ctx.check(rc, what)
+
+    def _raster(self):
+        h, st = self.ctx.handle, self._s()
+        self._chk(_lib.dressi_transform_batched(h, _p(self.pos), _p(self.vert_view), _p(self.mvp), self.V,
+                                                _p(self.pos_clip), st), "transform_batched")
+        self._chk(_lib.dressi_rasterize_batched(h, _p(self.pos_clip), _p(self.tris), _p(self.tri_view),
+                                                _p(self.views), self.n, self.V, self.T, self.H, self.W, 1, 0,
+                                                _p(self.tri_id), _p(self.bary), st), "rasterize_batched")
+
+    def _calibrate_bins(self):
+        for _ in range(4):
+            self._raster()
+            need = self.ctx.check_status()
+            if need <= 0:
+                return
+            cap = 1
+            while cap < need * 5 // 4:
+                cap <<= 1
+            self.ctx.reserve(0, cap)
+        raise RuntimeError("tile bins still overflow after growing them")
+
+    def forward(self):
+        h, st = self.ctx.handle, self._s()
+        H, W, V, T, ck = self.H, self.W, self.V, self.T, self._chk
+        ck(_lib.dressi_vertex_attrs(h, _p(self.pos), _p(self.tris), V, T, None, _p(self.adj), _p(self.vattr), st),
+           "vertex_attrs")
+        self._raster()
+        ck(_lib.dressi_interpolate(h, _p(self.vattr), 1, V, 6, _p(self.tris), T, _p(self.tri_id), _p(self.bary),
+                                   1, 1, H, W, _p(self.gbuf), st), "interpolate")
+        ck(_lib.dressi_interpolate(h, _p(self.uv), 1, self.uv.shape[0], 2, _p(self.uv_tris), T, _p(self.tri_id),
+                                   _p(self.bary), 1, 1, H, W, _p(self.uvbuf), st), "interpolate uv")
+        ck(_lib.dressi_texture(h, _p(self.tex), C.byref(self.desc), _p(self.uvbuf), _p(self.tri_id), 1, H, W,
+                               _p(self.samp), st), "texture")
+        ck(_lib.dressi_shade(h, Bd.SHADE_PHONG, C.byref(self._fin), _p(self.eye), _p(self.tri_id), 1, H * W,
+                             _p(self.layer_color), None, st), "shade")
+        ck(_lib.dressi_softras(h, _p(self.layer_color), None, _p(self.tri_id), 1, 1, H, W, 3, 1.0, 0.0,
+                               Bd.BLEND_HARD, _p(self.color), _p(self.sil), _p(self.E), st), "softras")
+
+    def loss_and_grad(self):
+        self._chk(_lib.dressi_loss_l2(self.ctx.handle, _p(self.color), _p(self.sil), _p(self.target),
+                                      _p(self.weight), 1, self.H, self.W, _p(self.loss), _p(self.g_color),
+                                      _p(self.g_sil), self._s()), "loss")
+
+    def backward(self):
+        h, st = self.ctx.handle, self._s()
+        H, W, V, T, ck, Ct = self.H, self.W, self.V, self.T, self._chk, self.Ct
+        ck(_lib.dressi_fragment_index(h, _p(self.tri_id), 1, 1, H, W, T, _p(self.frag_index), st), "fragment_index")
+        ck(_lib.dressi_softras_bwd(h, _p(self.layer_color), None, _p(self.tri_id), 1, 1, H, W, 3, 1.0, _p(self.E),
+                                   _p(self.g_color), _p(self.g_sil), _p(self.g_layer), None, st), "softras_bwd")
+        g = Bd.FragGrad()
+        g.normal, g.normal_stride = _cp(self.g_gbuf, 0), 6
+        g.pos, g.pos_stride = _cp(self.g_gbuf, 3), 6
+        g.albedo, g.albedo_stride = _cp(self.g_samp, 0), Ct
+        ck(_lib.dressi_shade_bwd(h, Bd.SHADE_PHONG, C.byref(self._fin), _p(self.eye), _p(self.tri_id), 1, H * W,
+                                 _p(self.g_layer), None, C.byref(g), st), "shade_bwd")
+        ck(_lib.dressi_texture_bwd(h, _p(self.tex), C.byref(self.desc), _p(self.uvbuf), _p(self.tri_id), 1, H, W,
+                                   _p(self.g_samp), _p(self.g_tex), _p(self.g_uvbuf), st), "texture_bwd")
+        ck(_lib.dressi_interpolate_bwd(h, _p(self.uv), 1, self.uv.shape[0], 2, _p(self.uv_tris), T,
+                                       _p(self.tri_id), _p(self.bary), 1, 1, H, W, _p(self.g_uvbuf), None,
+                                       _p(self.frag_index), _p(self.uv_adj), None, _p(self.g_bary_uv), st),
+           "interpolate_bwd uv")
+        ck(_lib.dressi_interpolate_bwd(h, _p(self.vattr), 1, V, 6, _p(self.tris), T, _p(self.tri_id), _p(self.bary),
+                                       1, 1, H, W, _p(self.g_gbuf), _p(self.g_bary_uv), _p(self.frag_index),
+                                       _p(self.adj), _p(self.g_vattr), _p(self.g_bary), st), "interpolate_bwd")
+        ck(_lib.dressi_rasterize_batched_bwd(h, _p(self.pos_clip), _p(self.tris), _p(self.tri_view), _p(self.views),
+                                             self.n, V, T, H, W, 1, 0, _p(self.tri_id), _p(self.g_bary),
+                                             _p(self.frag_index), _p(self.adj), _p(self.g_clip), st),
+           "rasterize_batched_bwd")
+        ck(_lib.dressi_transform_batched_bwd(h, _p(self.mvp), _p(self.vert_view), V, _p(self.g_clip),
+                                             _p(self.g_pos_t), st), "transform_batched_bwd")
+        ck(_lib.dressi_vertex_attrs_bwd(h, _p(self.pos), _p(self.tris), V, T, 6, _p(self.adj), _p(self.g_vattr),
+                                        _p(self.g_pos_t), _p(self.g_pos), st), "vertex_attrs_bwd")
+
+    def run(self):
+        self.forward()
+        self.loss_and_grad()
+        self.backward()
+
+    def rgba(self):
+        return torch.cat([self.color, self.sil[..., None]], -1).contiguous()
+
+    # per-view views of the batched buffers
+    def view_rect(self, i):
+        x0, y0, w, h = (int(v) for v in self.views_np[i])
+        return (slice(y0, y0 + h), slice(x0, x0 + w))
+
+    def view_tri_id(self, i):
+        """tri_id of view i in its own triangle numbering (-1 = empty)."""
+        t = self.tri_id[0, 0][self.view_rect(i)]
+        return torch.where(t >= 0, t - int(self.tbase[i]), t)
+
+    def view_grads(self, i):
+        return {"pos": self.g_pos[int(self.vbase[i]):int(self.vbase[i + 1])], "tex": self.g_tex[i]}
+
+
+def make_batch_target(scenes_list, device="cuda") -> BatchStep:
+    """Renders the targets of an uneven batch (perturbed meshes, target textures)."""
+    params = [{"pos": s.target_pos, "tex": s.target_tex} for s in scenes_list]
+    st = BatchStep(scenes_list, device, params=params)
     st.forward()
     return st

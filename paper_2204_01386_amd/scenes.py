@@ -233,6 +233,63 @@ def torus_knot(nu: int = 2048, nv: int = 256, p: int = 2, q: int = 3, radius: fl
     return pos.astype(np.float32), tris, uv.astype(np.float32), uv_tris.astype(np.int32)
 
 
+def uv_sphere(nu: int, nv: int, seed: int, amp: float = 0.05):
+    """Latitude-longitude sphere: nu columns (wrapping) x (nv + 1) rows from
+    pole to pole (the pole rows are coincident vertices), 2 nu nv triangles,
+    radius scaled per vertex by 1 + amp * smoothed N(0,1).  Per-corner UVs
+    (i / nu, j / nv) on an (nu+1) x (nv+1) grid (seam split)."""
+    i, j = np.meshgrid(np.arange(nu), np.arange(nv + 1), indexing="ij")
+    th, ph = 2 * math.pi * i / nu, math.pi * j / nv
+    pos = np.stack([np.sin(ph) * np.cos(th), np.cos(ph), np.sin(ph) * np.sin(th)], -1).reshape(-1, 3)
+    R = nv + 1
+    ii, jj = np.meshgrid(np.arange(nu), np.arange(nv), indexing="ij")
+    a = ii * R + jj
+    b = ((ii + 1) % nu) * R + jj
+    c = ((ii + 1) % nu) * R + jj + 1
+    d = ii * R + jj + 1
+    tris = np.stack([np.stack([a, b, c], -1), np.stack([a, c, d], -1)], 2).reshape(-1, 3).astype(np.int32)
+    rng = np.random.default_rng(seed)
+    pos = pos * (1.0 + amp * smooth_noise_edges(rng, tris, len(pos)))[:, None]
+    U, Vv = np.meshgrid(np.arange(nu + 1) / nu, np.arange(nv + 1) / nv, indexing="ij")
+    uv = np.stack([U, Vv], -1).reshape(-1, 2)
+    ua = ii * (nv + 1) + jj
+    ub = (ii + 1) * (nv + 1) + jj
+    uc = (ii + 1) * (nv + 1) + jj + 1
+    ud = ii * (nv + 1) + jj + 1
+    uv_tris = np.stack([np.stack([ua, ub, uc], -1), np.stack([ua, uc, ud], -1)], 2).reshape(-1, 3)
+    return pos.astype(np.float32), tris, uv.astype(np.float32), uv_tris.astype(np.int32)
+
+
+def noisy_torus(nu: int, nv: int, seed: int, R: float = 0.7, r: float = 0.3, amp: float = 0.05):
+    """Torus as an nu x nv grid wrapping both ways (2 nu nv triangles, outward
+    counter-clockwise), tube radius r * (1 + amp * smoothed N(0,1)) per vertex.
+    Per-corner UVs (i / nu, j / nv) on an (nu+1) x (nv+1) grid (seams split)."""
+    tris = grid_tris(nu, nv)
+    rng = np.random.default_rng(seed)
+    rad = r * (1.0 + amp * smooth_noise_edges(rng, tris, nu * nv)).reshape(nu, nv)
+    a = 2 * math.pi * np.arange(nu)[:, None] / nu
+    b = 2 * math.pi * np.arange(nv)[None, :] / nv
+    pos = np.stack([(R + rad * np.cos(b)) * np.cos(a), rad * np.sin(b), (R + rad * np.cos(b)) * np.sin(a)],
+                   -1).reshape(-1, 3)
+    i, j = np.meshgrid(np.arange(nu), np.arange(nv), indexing="ij")
+    ua = i * (nv + 1) + j
+    ub = (i + 1) * (nv + 1) + j
+    uc = (i + 1) * (nv + 1) + j + 1
+    ud = i * (nv + 1) + j + 1
+    uv_tris = np.stack([np.stack([ua, ub, uc], -1), np.stack([ua, uc, ud], -1)], 2).reshape(-1, 3)
+    # outward orientation: away from the core circle of radius R in the xz plane
+    c = pos[tris].mean(1)
+    n = np.cross(pos[tris[:, 1]] - pos[tris[:, 0]], pos[tris[:, 2]] - pos[tris[:, 0]])
+    ring = c[:, [0, 2]] / np.linalg.norm(c[:, [0, 2]], axis=1, keepdims=True) * R
+    out = c - np.stack([ring[:, 0], np.zeros(len(c)), ring[:, 1]], -1)
+    if (n * out).sum(1).mean() < 0:
+        tris = tris[:, [0, 2, 1]].copy()
+        uv_tris = uv_tris[:, [0, 2, 1]]
+    U, Vv = np.meshgrid(np.arange(nu + 1) / nu, np.arange(nv + 1) / nv, indexing="ij")
+    uv = np.stack([U, Vv], -1).reshape(-1, 2)
+    return pos.astype(np.float32), tris, uv.astype(np.float32), uv_tris.astype(np.int32)
+
+
 # --------------------------------------------------------------------------
 # textures
 # --------------------------------------------------------------------------
@@ -413,6 +470,42 @@ def config3(seed: int = 0, n_views: int = 16, H: int = 512, subdiv: int = 6,
     s.env = cube_env_map(env_size, seed + 11)
     s.extra["tangent"] = sphere_tangents(s.pos)
     return s
+
+
+def config4(seed: int = 0, n: int = 64, t_min: float = 1e3, t_max: float = 2e5,
+            sizes=(256, 512, 768, 1024), tex_size: int = 512) -> list:
+    """Uneven batch: n instances, T_i = round(exp(U(ln t_min, ln t_max)))
+    triangles, each a latitude-longitude sphere (nu = 2 nv) or a torus
+    (nu = 3 nv) with 2 nu nv close to T_i and radial noise as in config 2,
+    seen by its own camera (radius 3, random direction) at a resolution drawn
+    from `sizes`, with its own tex_size^2 RGBA value-noise texture; K=1,
+    Phong, repeat wrap.  Target: noise seed+1, texture seed+1.  Returns one
+    standalone Scene per instance."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        T = int(round(math.exp(rng.uniform(math.log(t_min), math.log(t_max)))))
+        torus_kind = bool(rng.integers(2))
+        res = int(sizes[rng.integers(len(sizes))])
+        s_i = 1000 * (seed + 1) + i
+        if torus_kind:
+            nv = max(3, int(round(math.sqrt(T / 6.0))))
+            nu = max(3, int(round(T / (2.0 * nv))))
+            p, tris, uv, uv_tris = noisy_torus(nu, nv, s_i)
+            tp, _, _, _ = noisy_torus(nu, nv, s_i + 1)
+        else:
+            nv = max(3, int(round(math.sqrt(T / 4.0))))
+            nu = max(3, int(round(T / (2.0 * nv))))
+            p, tris, uv, uv_tris = uv_sphere(nu, nv, s_i)
+            tp, _, _, _ = uv_sphere(nu, nv, s_i + 1)
+        eyes = camera_ring(1, s_i)
+        sc = Scene(f"inst{i}-{'torus' if torus_kind else 'sphere'}{nu}x{nv}-{res}", p, tris, view_proj(eyes),
+                   eyes.astype(np.float32), res, res, 1, 0.0, "phong", uv=uv, uv_tris=uv_tris,
+                   tex=value_noise(tex_size, tex_size, 4, s_i), target_pos=tp,
+                   target_tex=value_noise(tex_size, tex_size, 4, s_i + 1))
+        sc.extra["wrap"] = (0, 0)   # repeat in u and v
+        out.append(sc)
+    return out
 
 
 def config5(seed: int = 0, n_views: int = 8, H: int = 2048, nu: int = 2048, nv: int = 256,

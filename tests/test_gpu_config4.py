@@ -1,0 +1,110 @@
+"""Uneven batches: many meshes of different sizes, each seen by its own camera
+at its own resolution, rendered and differentiated as one batch (every stage
+one launch for all views, views packed into rectangles of one image).
+
+Every view of the batch must give exactly what a standalone render of that
+scene gives (the same triangle ids, image and gradients, bit for bit: views
+are snapped in their own frame and drawn in tile-aligned rectangles, so every
+sum runs over the same terms in the same order), and the standalone render is
+checked against the oracle."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import step as ostep
+from paper_2204_01386_amd import scenes
+from test_gpu_parity import assert_grad_close, assert_vals_close, host
+
+pytestmark = pytest.mark.gpu
+
+
+def _standalone(scene):
+    from paper_2204_01386_amd.pipeline import Step, make_target
+    st = Step(scene, target=make_target(scene))
+    st.run()
+    torch.cuda.synchronize()
+    return st
+
+
+def _batched(scene_list):
+    from paper_2204_01386_amd.pipeline import BatchStep, make_batch_target
+    bs = BatchStep(scene_list, target=make_batch_target(scene_list))
+    bs.run()
+    torch.cuda.synchronize()
+    return bs
+
+
+def _compare_view(bs, i, st):
+    rect = bs.view_rect(i)
+    assert np.array_equal(host(bs.view_tri_id(i)), host(st.tri_id[0, 0])), f"view {i}: tri_id differs"
+    assert np.array_equal(host(bs.rgba()[0][rect]), host(st.rgba()[0])), f"view {i}: image differs"
+    g = bs.view_grads(i)
+    gs = st.grads()
+    assert np.array_equal(host(g["pos"]), host(gs["pos"])), f"view {i}: position gradient differs"
+    assert np.array_equal(host(g["tex"]), host(gs["tex"])), f"view {i}: texture gradient differs"
+
+
+@pytest.fixture(scope="module")
+def small_batch():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return scenes.config4(seed=3, n=6, t_min=200, t_max=2e4, sizes=(128, 256), tex_size=128)
+
+
+def test_batch_small_matches_standalone_and_oracle(small_batch):
+    bs = _batched(small_batch)
+    losses = []
+    for i, sc in enumerate(small_batch):
+        st = _standalone(sc)
+        _compare_view(bs, i, st)
+        losses.append(float(host(st.loss)[0]))
+        o_st, _, o_g = ostep.step(sc)
+        assert np.array_equal(host(st.tri_id), o_st["tid"]), f"view {i}: tri_id differs from the oracle"
+        assert_vals_close(host(st.rgba()), o_st["rgba"], what=f"view {i} image")
+        assert_grad_close(host(st.grads()["pos"]), o_g["pos"], what=f"view {i} grad pos")
+        assert_grad_close(host(st.grads()["tex"]), o_g["tex"], what=f"view {i} grad texture")
+    L = float(host(bs.loss)[0])
+    assert abs(L - sum(losses)) <= 1e-5 * sum(losses), (L, sum(losses))
+
+
+def test_batch_config4_full_matches_standalone():
+    sl = scenes.config4()
+    bs = _batched(sl)
+    assert bs.n == 64 and bs.T > 10 ** 6
+    rng = np.random.default_rng(0)
+    # every view's triangle ids and image; gradients of a sample of views
+    sample = set(rng.choice(64, 8, replace=False).tolist())
+    for i, sc in enumerate(sl):
+        st = _standalone(sc)
+        rect = bs.view_rect(i)
+        assert np.array_equal(host(bs.view_tri_id(i)), host(st.tri_id[0, 0])), f"view {i}: tri_id differs"
+        assert np.array_equal(host(bs.rgba()[0][rect]), host(st.rgba()[0])), f"view {i}: image differs"
+        if i in sample:
+            _compare_view(bs, i, st)
+        del st
+    # the smallest view against the oracle
+    i = int(np.argmin([s.tris.shape[0] * s.H for s in sl]))
+    o_st, _, o_g = ostep.step(sl[i])
+    assert np.array_equal(host(bs.view_tri_id(i)), o_st["tid"][0, 0])
+    assert_vals_close(host(bs.rgba()[0][bs.view_rect(i)]), o_st["rgba"][0], what="image")
+    assert_grad_close(host(bs.view_grads(i)["pos"]), o_g["pos"], what="grad pos")
+
+
+def test_batch_deterministic_and_graph_replay(small_batch):
+    bs = _batched(small_batch)
+    ref = host(bs.g_pos).copy(), host(bs.g_tex).copy()
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        bs.run()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g):
+        bs.run()
+    for rep in range(3):
+        bs.g_pos.fill_(7.0)
+        bs.g_tex.fill_(7.0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(host(bs.g_pos), ref[0]) and np.array_equal(host(bs.g_tex), ref[1]), f"replay {rep}"
