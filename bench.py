@@ -42,6 +42,9 @@ def parse():
     ap.add_argument("--no-multiview", dest="multiview", action="store_false",
                     help="skip the 16-view batched-vs-plain measurement")
     ap.add_argument("--multiview-steps", type=int, default=30)
+    ap.add_argument("--no-uneven", dest="uneven", action="store_false",
+                    help="skip the 64-instance uneven batch measurement")
+    ap.add_argument("--uneven-steps", type=int, default=20)
     ap.add_argument("--copy-ref", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of MIB MiB (reference for HBM counters)")
     return ap.parse_args()
@@ -317,6 +320,103 @@ def measure(scene, steps, warmup, prof_steps, plain_steps_min=10):
     return res
 
 
+def measure_batch(scene_list, steps, warmup, prof_steps):
+    """The uneven batch: one captured step of the whole batch (every stage one
+    launch) against a loop of standalone per-view steps issued eagerly."""
+    import ctypes as C
+
+    import torch
+
+    from paper_2204_01386_amd import binding as Bd
+    from paper_2204_01386_amd.pipeline import BatchStep, Step, autotune, make_batch_target, make_target
+
+    bs = BatchStep(scene_list, target=make_batch_target(scene_list))
+    tuned = autotune(bs)
+    ctx = Bd.context()
+    for _ in range(3):
+        bs.run()
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        bs.run()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(graph):
+        bs.run()
+    for _ in range(warmup):
+        graph.replay()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(steps):
+        graph.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    ms_batched = e0.elapsed_time(e1) / steps
+    if ctx.check_status() != 0:
+        raise SystemExit("tile-bin capacity overflow in the timed region")
+    del graph
+    # plain: one standalone step per view, eager
+    plain = [Step(sc, target=make_target(sc)) for sc in scene_list]
+    for ps in plain:
+        autotune(ps, reps=2)
+        ps.run()
+    torch.cuda.synchronize()
+    n_plain = max(3, steps // 4)
+    e0.record()
+    for _ in range(n_plain):
+        for ps in plain:
+            ps.run()
+    e1.record()
+    torch.cuda.synchronize()
+    ms_plain = e0.elapsed_time(e1) / n_plain
+    step_bytes = 0
+    for ps in plain:
+        step_bytes += sum(call_bytes(Shapes(ps, int((ps.tri_id >= 0).sum().item()))).values())
+    del plain
+    # per-kernel times of the batched step
+    cap = 400 * max(prof_steps, 1)
+    Bd._lib.dressi_profile_start(cap)
+    for _ in range(prof_steps):
+        bs.run()
+    torch.cuda.synchronize()
+    names = (C.c_char_p * cap)()
+    ms = (C.c_float * cap)()
+    n = Bd._lib.dressi_profile_read(names, ms, cap)
+    Bd._lib.dressi_profile_start(0)
+    per = {}
+    for i in range(n):
+        k = names[i].decode()
+        per[k] = per.get(k, 0.0) + ms[i]
+    table = sorted(((k, v / max(prof_steps, 1)) for k, v in per.items()), key=lambda x: -x[1])
+    return {"ms_per_step": ms_batched, "plain_ms_per_step": ms_plain, "step_alg_bytes": step_bytes,
+            "table": table, "T": bs.T, "pixels": int(sum(s.H * s.W for s in scene_list)),
+            "canvas": (bs.W, bs.H), "tuned": tuned}
+
+
+def uneven_line(steps, prof_steps):
+    from paper_2204_01386_amd import scenes
+    sl = scenes.config4()
+    m = measure_batch(sl, steps, 3, prof_steps)
+    return {"workload": "64 uneven instances: UV spheres and tori of 1k-200k triangles (log-uniform, "
+                        f"{m['T']:,} in all), {{256,512,768,1024}}^2 views ({m['pixels'] / 1e6:.1f} Mpix, "
+                        f"packed into a {m['canvas'][0]}x{m['canvas'][1]} image), 512^2 RGBA texture each, "
+                        "K=1, Phong, per-view L2",
+            "ms_per_step": round(m["ms_per_step"], 4),
+            "value": round(m["pixels"] / (m["ms_per_step"] * 1e-3) / 1e6, 2), "unit": "Mpix/s",
+            "tris_per_s": round(m["T"] / (m["ms_per_step"] * 1e-3), 1),
+            "plain_ms_per_step": round(m["plain_ms_per_step"], 4),
+            "batched_vs_plain_speedup": round(m["plain_ms_per_step"] / m["ms_per_step"], 3),
+            "step_alg_bytes": m["step_alg_bytes"],
+            "step_hbm_frac": round(m["step_alg_bytes"] / (m["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "autotune": {"hard_raster": ["triangle-parallel", "pixel-parallel"][m["tuned"]["hard_raster"]],
+                         "raster_ms": {["triangle-parallel", "pixel-parallel"][k]: round(v, 4)
+                                       for k, v in m["tuned"]["ms"].items()}},
+            "kernels": [{"kernel": k, "ms_per_step": round(v, 5)} for k, v in m["table"][:12]]}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -355,7 +455,7 @@ def main():
 
     # ---- the 16-view batched configuration beside its per-view form -------
     multi = None
-    if args.multiview and args.config != 3:
+    if args.multiview and args.config == 2:
         s3, d3 = scene_for(3)
         m3 = measure(s3, args.multiview_steps, 5, args.profile_steps // 4, plain_steps_min=3)
         z3 = Shapes(m3["step"], m3["cov"])
@@ -373,6 +473,9 @@ def main():
                              for k, a, b, c in m3["table"][:12]],
                  "launches": [{"launch": k, "ms": round(a, 5)} for k, a in m3["launches"][:16]]}
         del m3
+
+    # ---- the uneven 64-instance batch beside its per-instance form ---------
+    uneven = uneven_line(args.uneven_steps, max(1, args.profile_steps // 4)) if args.uneven and args.config == 2 else None
 
     # ---- CPU baseline: the oracle's step on the same workload --------------
     cpu = None
@@ -425,6 +528,7 @@ def main():
                      "ms_per_launch": round(dom[2], 5)},
         "cpu_baseline": cpu,
         "multiview": multi,
+        "uneven": uneven,
         "kernels": kernel_rows,
         "launches": launch_rows,
     }

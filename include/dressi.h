@@ -89,6 +89,18 @@ size_t dressi_scratch_bytes(int B, int V, int T, int H, int W, int K, float r,
  * receives the capacity that call required (may be NULL). */
 int dressi_check_status(dressi_ctx *ctx, int64_t *needed, void *stream);
 
+/* Tuning knobs that change speed, never results (an autotuner times the
+ * candidates on the real workload and keeps the fastest):
+ * DRESSI_TUNE_BIN_CAPACITY: triangles per 16x16 tile bin (0 = automatic;
+ *   too small a capacity is reported by dressi_check_status);
+ * DRESSI_TUNE_HARD_RASTER: hard rasterization (r = 0) strategy, 0 =
+ *   triangle-parallel per tile with LDS atomics (small triangles), 1 =
+ *   pixel-parallel with per-pixel lists in registers (large triangles).
+ *   Both select exactly the same layers. */
+#define DRESSI_TUNE_BIN_CAPACITY 1
+#define DRESSI_TUNE_HARD_RASTER 2
+int dressi_tune(dressi_ctx *ctx, int key, int64_t value);
+
 /* Kernel timing for measurement: while on, every kernel launch of the library
  * gets a start/stop HIP event pair that the runtime stamps from the launch's
  * own dispatch (the kernel's execution time alone).  dressi_profile_start(n) turns it

@@ -26,6 +26,7 @@ if not os.path.exists(LIB_PATH):
 _lib = C.CDLL(LIB_PATH)
 
 TEX_2D, TEX_CUBE, TEX_2D_ARRAY = 0, 1, 2
+TUNE_BIN_CAPACITY, TUNE_HARD_RASTER = 1, 2
 WRAP_REPEAT, WRAP_CLAMP = 0, 1
 BLEND_HSR, BLEND_AA, BLEND_SOFTRAS, BLEND_HARD = 0, 1, 2, 3
 
@@ -79,6 +80,7 @@ _SIG = {
     "dressi_shade_bwd": [_vp, _i, _vp, _vp, _vp, _i, _i64, _vp, _vp, _vp, _vp],
     "dressi_loss_l2": [_vp, _vp, _vp, _vp, _vp, _i, _i, _i, _vp, _vp, _vp, _vp],
     "dressi_transform_batched": [_vp, _vp, _vp, _vp, _i, _vp, _vp],
+    "dressi_tune": [_vp, _i, _i64],
     "dressi_transform_batched_bwd": [_vp, _vp, _vp, _i, _vp, _vp, _vp],
     "dressi_rasterize_batched": [_vp, _vp, _vp, _vp, _vp, _i, _i, _i, _i, _i, _i, _i, _vp, _vp, _vp],
     "dressi_rasterize_batched_bwd": [_vp, _vp, _vp, _vp, _vp, _i, _i, _i, _i, _i, _i, _i, _vp, _vp, _vp, _vp,
@@ -125,6 +127,9 @@ class Context:
 
     def reserve(self, nbytes: int = 0, bin_entries: int = 0):
         self.check(_lib.dressi_reserve(self.handle, nbytes, bin_entries), "dressi_reserve")
+
+    def tune(self, key: int, value: int):
+        self.check(_lib.dressi_tune(self.handle, key, value), "dressi_tune")
 
     def check_status(self, stream=None):
         needed = C.c_int64(0)

@@ -114,6 +114,22 @@ extern "C" int dressi_reserve(dressi_ctx *ctx, size_t bytes, int64_t bin_entries
     return grow(ctx, bytes);
 }
 
+extern "C" int dressi_tune(dressi_ctx *ctx, int key, int64_t value) {
+    if (!ctx) return DRESSI_EINVAL;
+    switch (key) {
+    case DRESSI_TUNE_BIN_CAPACITY:
+        if (value < 0 || value > (1 << 26)) return dressi_fail(ctx, DRESSI_EINVAL, "tune: bad bin capacity");
+        ctx->bin_capacity = value;   // 0 = automatic
+        return DRESSI_OK;
+    case DRESSI_TUNE_HARD_RASTER:
+        if (value != 0 && value != 1) return dressi_fail(ctx, DRESSI_EINVAL, "tune: hard raster is 0 or 1");
+        ctx->hard_raster = (int)value;
+        return DRESSI_OK;
+    default:
+        return dressi_fail(ctx, DRESSI_EINVAL, "tune: unknown key");
+    }
+}
+
 extern "C" int dressi_check_status(dressi_ctx *ctx, int64_t *needed, void *stream) {
     if (!ctx) return DRESSI_EINVAL;
     int64_t h[4];

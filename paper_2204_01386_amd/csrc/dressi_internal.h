@@ -19,6 +19,7 @@ struct dressi_ctx {
     void *scratch = nullptr;    // device arena, reused by every call on this context
     size_t scratch_bytes = 0;
     int64_t bin_capacity = 0;   // triangles per screen tile bin (0 = automatic)
+    int hard_raster = 0;        // hard rasterization: 0 triangle-parallel, 1 pixel-parallel
     int64_t *status = nullptr;  // device: [0] overflow flag, [1] bin capacity needed
     int32_t *counters = nullptr;  // device counters kept at zero between calls
     size_t counters_n = 0;

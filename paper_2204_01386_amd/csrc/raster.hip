@@ -355,7 +355,7 @@ __device__ __forceinline__ float rl_segmin_i(const int *qx, const int *qy, const
 
 // Merges the candidate fragment of triangle t at this lane's pixel.  MAYHARD
 // is false when no pixel centre of the wavefront can be inside the triangle.
-template <int K, bool MAYHARD, typename TE>
+template <int K, bool MAYHARD, typename TE, bool SOFT = true>
 __device__ __forceinline__ void rl_merge(const TriSetup &s, const TE *E, const float *el, int t, int px,
                                          int py, float dscale, float r, float reach, float *key, int *id,
                                          const int *qx = nullptr, const int *qy = nullptr,
@@ -375,6 +375,7 @@ __device__ __forceinline__ void rl_merge(const TriSetup &s, const TE *E, const f
         if (!(z > 0.0f && z < 1.0f)) return;
         kf = 0.5f * z;
     } else {
+        if (!SOFT) return;
         // The distance to the triangle is at least the distance -E_i / |e_i|
         // to the line of any edge the pixel lies outside of.  A soft fragment
         // enters the list only if its key 0.5 + dn/2 is at most the list's
@@ -423,7 +424,7 @@ __device__ __forceinline__ void rl_merge(const TriSetup &s, const TE *E, const f
     }
 }
 
-template <int K>
+template <int K, bool SOFT>
 __global__ void __launch_bounds__(DRESSI_TILE_PIX) __attribute__((amdgpu_waves_per_eu(5)))
     k_raster_list(const TriSetup *__restrict__ setup, int32_t *__restrict__ counts,
                   const int32_t *__restrict__ bins, int cap, int T, int H, int W, int ntx, int nt,
@@ -474,7 +475,7 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX) __attribute__((amdgpu_waves_p
     int wmax_bits = __float_as_int(2.0f);   // bound on the strip's K-th keys (they only decrease)
     int gap_max = 0x3fffffff;               // soft-only triangles farther (pixels) than this are culled
 
-    for (int walk = 0; walk < 3; walk++) {
+    for (int walk = 0; walk < (SOFT ? 3 : 1); walk++) {   // hard only: covering triangles
         for (int c0 = 0; c0 < nbin; c0 += RL_BATCH) {
             const int n = min(RL_BATCH, nbin - c0);
             if (walk == 0 || nbin > RL_BATCH) {   // a single batch stays staged
@@ -563,15 +564,17 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX) __attribute__((amdgpu_waves_p
                             E[i] = __mul24(ex[i], qy[a]) - __mul24(ey[i], qx[a]);
                         }
                         if (walk == 0)
-                            rl_merge<K, true>(s, E, el, t, px, py, dscale, r, reach, key, id, qx, qy, ex, ey, len2);
+                            rl_merge<K, true, int, SOFT>(s, E, el, t, px, py, dscale, r, reach, key, id, qx, qy, ex,
+                                                         ey, len2);
                         else
-                            rl_merge<K, false>(s, E, el, t, px, py, dscale, r, reach, key, id, qx, qy, ex, ey, len2);
+                            rl_merge<K, false, int, SOFT>(s, E, el, t, px, py, dscale, r, reach, key, id, qx, qy, ex,
+                                                          ey, len2);
                     } else {
                         double E[3];
 #pragma unroll
                         for (int i = 0; i < 3; i++) E[i] = dr_edge(s.X, s.Y, i, px, py);
-                        if (walk == 0) rl_merge<K, true>(s, E, el, t, px, py, dscale, r, reach, key, id);
-                        else rl_merge<K, false>(s, E, el, t, px, py, dscale, r, reach, key, id);
+                        if (walk == 0) rl_merge<K, true, double, SOFT>(s, E, el, t, px, py, dscale, r, reach, key, id);
+                        else rl_merge<K, false, double, SOFT>(s, E, el, t, px, py, dscale, r, reach, key, id);
                     }
                 }
                 // keys only decrease: refresh the strip's bounds
@@ -586,16 +589,23 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX) __attribute__((amdgpu_waves_p
     }
     __syncthreads();
     if (p == 0) counts[bt] = 0;   // every lane has read it before the first barrier
-    resolve_store<K, true>(sv, key, id, b, x, y, px, py, H, W, dscale, tri_id, bary, dist);
+    resolve_store<K, SOFT>(sv, key, id, b, x, y, px, py, H, W, dscale, tri_id, bary, dist);
 }
 
+// Hard rasterization has two strategies with identical results (the layer
+// selection does not depend on visiting order): triangle-parallel per tile
+// with LDS atomics (small triangles) or pixel-parallel with register lists
+// (large triangles); dressi_tune picks one per context.
 template <int K>
-static void launch_raster_k(bool soft, dim3 g, hipStream_t st, const TriSetup *setup, int32_t *counts,
-                            const int32_t *bins, int cap, int T, int H, int W, int ntx, int nt, float r,
-                            int32_t *tid, float2 *bary, float *dist) {
+static void launch_raster_k(bool soft, int hard_pix, dim3 g, hipStream_t st, const TriSetup *setup,
+                            int32_t *counts, const int32_t *bins, int cap, int T, int H, int W, int ntx, int nt,
+                            float r, int32_t *tid, float2 *bary, float *dist) {
     if (soft)
-        DR_LAUNCH("k_raster_list", (k_raster_list<K>), g, DRESSI_TILE_PIX, 0, st, setup, counts, bins, cap, T,
-                  H, W, ntx, nt, r, tid, bary, dist);
+        DR_LAUNCH("k_raster_list", (k_raster_list<K, true>), g, DRESSI_TILE_PIX, 0, st, setup, counts, bins, cap,
+                  T, H, W, ntx, nt, r, tid, bary, dist);
+    else if (hard_pix)
+        DR_LAUNCH("k_raster_list", (k_raster_list<K, false>), g, DRESSI_TILE_PIX, 0, st, setup, counts, bins,
+                  cap, T, H, W, ntx, nt, r, tid, bary, dist);
     else
         DR_LAUNCH("k_raster", (k_raster<K, false>), g, DRESSI_TILE_PIX, 0, st, setup, counts, bins, cap, T, H,
                   W, ntx, nt, r, tid, bary, dist);
@@ -671,12 +681,13 @@ static int rasterize_impl(dressi_ctx *ctx, const float *pos_clip, const int32_t 
                   nt, cap, setup, counts, bins, reinterpret_cast<unsigned long long *>(ctx->status));
     dim3 g((unsigned)(B * nt));
     float2 *b2 = reinterpret_cast<float2 *>(bary);
+    const int hp = ctx->hard_raster;
     switch (K) {
-    case 1: launch_raster_k<1>(soft, g, st, setup, counts, bins, cap, T, H, W, ntx, nt, r, tri_id, b2, dist); break;
-    case 2: launch_raster_k<2>(soft, g, st, setup, counts, bins, cap, T, H, W, ntx, nt, r, tri_id, b2, dist); break;
-    case 3: launch_raster_k<3>(soft, g, st, setup, counts, bins, cap, T, H, W, ntx, nt, r, tri_id, b2, dist); break;
-    case 4: launch_raster_k<4>(soft, g, st, setup, counts, bins, cap, T, H, W, ntx, nt, r, tri_id, b2, dist); break;
-    default: launch_raster_k<5>(soft, g, st, setup, counts, bins, cap, T, H, W, ntx, nt, r, tri_id, b2, dist); break;
+    case 1: launch_raster_k<1>(soft, hp, g, st, setup, counts, bins, cap, T, H, W, ntx, nt, r, tri_id, b2, dist); break;
+    case 2: launch_raster_k<2>(soft, hp, g, st, setup, counts, bins, cap, T, H, W, ntx, nt, r, tri_id, b2, dist); break;
+    case 3: launch_raster_k<3>(soft, hp, g, st, setup, counts, bins, cap, T, H, W, ntx, nt, r, tri_id, b2, dist); break;
+    case 4: launch_raster_k<4>(soft, hp, g, st, setup, counts, bins, cap, T, H, W, ntx, nt, r, tri_id, b2, dist); break;
+    default: launch_raster_k<5>(soft, hp, g, st, setup, counts, bins, cap, T, H, W, ntx, nt, r, tri_id, b2, dist); break;
     }
     return dressi_launch_check(ctx, "rasterize");
 }

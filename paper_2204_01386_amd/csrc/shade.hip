@@ -460,17 +460,21 @@ extern "C" int dressi_shade_bwd(dressi_ctx *ctx, int mode, const dressi_frag_in 
 // L2 loss with a fixed-order reduction
 // ---------------------------------------------------------------------------
 #define LOSS_BS 256
-#define LOSS_MAX_BLOCKS 128   // few blocks: one completion atomic each
+#define LOSS_PER_THREAD 4
+#define LOSS_MAX_BLOCKS 4096
 
+// Squared differences (and their gradients) of a contiguous range of pixels
+// per block, reduced in a fixed tree order to one partial per block; a second
+// one-block kernel adds the partials in block order.  No atomics, no fences.
 __global__ void __launch_bounds__(LOSS_BS)
     k_loss_l2(const float *__restrict__ color, const float *__restrict__ sil,
-              const float *__restrict__ target, const float *__restrict__ weight, int64_t n, float inv,
-              float *__restrict__ grad_color, float *__restrict__ grad_sil, float *__restrict__ partial,
-              int32_t *__restrict__ done, float *__restrict__ loss) {
+              const float *__restrict__ target, const float *__restrict__ weight, int64_t n, int64_t per_block,
+              float inv, float *__restrict__ grad_color, float *__restrict__ grad_sil,
+              float *__restrict__ partial) {
     __shared__ float red[LOSS_BS];
-    __shared__ int last;
     float acc = 0.0f;
-    for (int64_t i = (int64_t)blockIdx.x * LOSS_BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * LOSS_BS) {
+    const int64_t i0 = (int64_t)blockIdx.x * per_block, i1 = min(n, i0 + per_block);
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += LOSS_BS) {
         float4 t = reinterpret_cast<const float4 *>(target)[i];
         float d0 = color[3 * i] - t.x, d1 = color[3 * i + 1] - t.y, d2 = color[3 * i + 2] - t.z;
         float d3 = sil[i] - t.w;
@@ -491,27 +495,21 @@ __global__ void __launch_bounds__(LOSS_BS)
         if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        partial[blockIdx.x] = red[0];
-        __threadfence();
-        last = atomicAdd(done, 1) == (int)gridDim.x - 1;
-    }
-    __syncthreads();
-    if (!last) return;
-    // the last block to finish sums the per-block partials in a fixed order
-    __threadfence();
-    float a2 = 0.0f;
-    for (int i = threadIdx.x; i < (int)gridDim.x; i += LOSS_BS) a2 += __builtin_nontemporal_load(&partial[i]);
-    red[threadIdx.x] = a2;
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(LOSS_BS)
+    k_loss_sum(const float *__restrict__ partial, int nb, float scale, float *__restrict__ loss) {
+    __shared__ float red[LOSS_BS];
+    float a = 0.0f;
+    for (int i = threadIdx.x; i < nb; i += LOSS_BS) a += partial[i];
+    red[threadIdx.x] = a;
     __syncthreads();
     for (int s = LOSS_BS / 2; s > 0; s >>= 1) {
         if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        loss[0] = weight ? red[0] : red[0] * inv;
-        *done = 0;   // leave the counter at zero
-    }
+    if (threadIdx.x == 0) loss[0] = red[0] * scale;
 }
 
 extern "C" int dressi_loss_l2(dressi_ctx *ctx, const float *color, const float *sil, const float *target,
@@ -523,18 +521,24 @@ extern "C" int dressi_loss_l2(dressi_ctx *ctx, const float *color, const float *
     if (!loss) return dressi_fail(ctx, DRESSI_EINVAL, "loss_l2: null loss");
     if (n > 0 && (!color || !sil || !target)) return dressi_fail(ctx, DRESSI_EINVAL, "loss_l2: null input");
     hipStream_t st = (hipStream_t)stream;
-    int nb = (int)((n + LOSS_BS - 1) / LOSS_BS);
-    if (nb > LOSS_MAX_BLOCKS) nb = LOSS_MAX_BLOCKS;
+    // blocks of at least LOSS_PER_THREAD pixels per thread, at most LOSS_MAX_BLOCKS
+    int64_t per = (int64_t)LOSS_BS * LOSS_PER_THREAD;
+    int64_t nb = (n + per - 1) / per;
+    if (nb > LOSS_MAX_BLOCKS) {
+        nb = LOSS_MAX_BLOCKS;
+        per = (n + nb - 1) / nb;
+        per = (per + LOSS_BS - 1) / LOSS_BS * LOSS_BS;
+        nb = (n + per - 1) / per;
+    }
     if (nb < 1) nb = 1;
     Carver c;
-    size_t o_p = c.take(sizeof(float) * nb);
+    size_t o_p = c.take(sizeof(float) * (size_t)nb);
     int rc = dressi_scratch(ctx, c.off, st);
-    if (rc) return rc;
-    rc = dressi_counters(ctx, 1, st);
     if (rc) return rc;
     float *partial = at<float>(ctx->scratch, o_p);
     float inv = 1.0f / (4.0f * (float)(n > 0 ? n : 1));
-    DR_LAUNCH("k_loss_l2", (k_loss_l2), nb, LOSS_BS, 0, st, color, sil, target, weight, n, inv, grad_color,
-              grad_sil, partial, ctx->counters, loss);
+    DR_LAUNCH("k_loss_l2", (k_loss_l2), (int)nb, LOSS_BS, 0, st, color, sil, target, weight, n, per, inv,
+              grad_color, grad_sil, partial);
+    DR_LAUNCH("k_loss_sum", (k_loss_sum), 1, LOSS_BS, 0, st, partial, (int)nb, weight ? 1.0f : inv, loss);
     return dressi_launch_check(ctx, "loss_l2");
 }

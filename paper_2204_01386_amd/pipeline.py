@@ -148,19 +148,24 @@ class Step:
         self.frag_index = torch.empty(nbytes, dtype=torch.uint8, device=dev)
         self._fin = self._frag_in()
         self._fin_dir = self._frag_in(with_env=False)
+        self.hard_raster = None     # rasterization strategy chosen by autotune() (None: triangle-parallel)
         self._calibrate_bins()
+
+    def _raster(self):
+        h, st = self.ctx.handle, self._s()
+        self.ctx.tune(Bd.TUNE_HARD_RASTER, self.hard_raster or 0)
+        self._chk(_lib.dressi_transform(h, _p(self.pos), _p(self.mvp), self.B, self.V, _p(self.pos_clip), st),
+                  "transform")
+        self._chk(_lib.dressi_rasterize(h, _p(self.pos_clip), _p(self.tris), self.B, self.V, self.T, self.H,
+                                        self.W, self.K, self.r, 0, _p(self.tri_id), _p(self.bary),
+                                        _p(self.dist), st), "rasterize")
 
     def _calibrate_bins(self):
         """Rasterizes once and grows the tile-bin capacity until no tile
         overflows (dense or strongly overlapping geometry), so that later
         steps, captured or not, need no check."""
-        h, st = self.ctx.handle, self._s()
         for _ in range(4):
-            self._chk(_lib.dressi_transform(h, _p(self.pos), _p(self.mvp), self.B, self.V, _p(self.pos_clip), st),
-                      "transform")
-            self._chk(_lib.dressi_rasterize(h, _p(self.pos_clip), _p(self.tris), self.B, self.V, self.T, self.H,
-                                            self.W, self.K, self.r, 0, _p(self.tri_id), _p(self.bary),
-                                            _p(self.dist), st), "rasterize")
+            self._raster()
             need = self.ctx.check_status()
             if need <= 0:
                 return
@@ -200,9 +205,7 @@ class Step:
         ck = self._chk
         ck(_lib.dressi_vertex_attrs(h, _p(self.pos), _p(self.tris), V, T, _p(self.extra), _p(self.adj),
                                     _p(self.vattr), s), "vertex_attrs")
-        ck(_lib.dressi_transform(h, _p(self.pos), _p(self.mvp), B, V, _p(self.pos_clip), s), "transform")
-        ck(_lib.dressi_rasterize(h, _p(self.pos_clip), _p(self.tris), B, V, T, H, W, K, self.r, 0,
-                                 _p(self.tri_id), _p(self.bary), _p(self.dist), s), "rasterize")
+        self._raster()
         ck(_lib.dressi_interpolate(h, _p(self.vattr), 1, V, self.Cv, _p(self.tris), T, _p(self.tri_id),
                                    _p(self.bary), B, K, H, W, _p(self.gbuf), s), "interpolate")
         if self.uv is not None:
@@ -434,6 +437,7 @@ class BatchStep:
         fi.albedo, fi.albedo_stride, fi.albedo_channels = _cp(self.samp, 0), Ct, 4
         fi.tri_eye = C.c_void_p(self.tri_view.data_ptr())
         self._fin = fi
+        self.hard_raster = None
         self._calibrate_bins()
 
     def _s(self):
@@ -445,6 +449,7 @@ class BatchStep:
 
     def _raster(self):
         h, st = self.ctx.handle, self._s()
+        self.ctx.tune(Bd.TUNE_HARD_RASTER, self.hard_raster or 0)
         self._chk(_lib.dressi_transform_batched(h, _p(self.pos), _p(self.vert_view), _p(self.mvp), self.V,
                                                 _p(self.pos_clip), st), "transform_batched")
         self._chk(_lib.dressi_rasterize_batched(h, _p(self.pos_clip), _p(self.tris), _p(self.tri_view),
@@ -543,3 +548,49 @@ def make_batch_target(scenes_list, device="cuda") -> BatchStep:
     st = BatchStep(scenes_list, device, params=params)
     st.forward()
     return st
+
+
+# ---------------------------------------------------------------------------
+# autotuning
+# ---------------------------------------------------------------------------
+def autotune(step, reps: int = 5) -> dict:
+    """Picks the hard-rasterization strategy (triangle-parallel or
+    pixel-parallel tiles) and the tile-bin capacity for this step's own
+    geometry by timing each candidate's transform + rasterization on the
+    device, after checking that it selects exactly the same layers as the
+    first candidate (it must: the choice changes speed only).  The choice is
+    stored on the step and applied at every later rasterization, so it is
+    also what a captured graph records.  Soft rasterization (r > 0) has one
+    strategy; only its bin capacity is tuned."""
+    ctx = step.ctx
+    strategies = [0, 1] if getattr(step, "r", 0.0) == 0 else [None]
+    need = 0
+    results = {}
+    ref = None
+    for hr in strategies:
+        step.hard_raster = hr
+        step._raster()
+        torch.cuda.synchronize()
+        need = max(need, ctx.check_status())
+        tid = step.tri_id.clone()
+        if ref is None:
+            ref = tid
+        elif not torch.equal(ref, tid):
+            raise RuntimeError(f"rasterization strategy {hr} selects different layers")
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            step._raster()
+        e1.record()
+        torch.cuda.synchronize()
+        results[hr] = e0.elapsed_time(e1) / reps
+    best = min(results, key=results.get)
+    step.hard_raster = best
+    # bin capacity: the smallest power of two above 5/4 of the fullest tile
+    cap = 0
+    if need > 0:
+        cap = 1
+        while cap < need * 5 // 4:
+            cap <<= 1
+        ctx.reserve(0, cap)
+    return {"hard_raster": best, "ms": results, "bin_capacity": cap}

@@ -108,3 +108,28 @@ def test_batch_deterministic_and_graph_replay(small_batch):
         g.replay()
         torch.cuda.synchronize()
         assert np.array_equal(host(bs.g_pos), ref[0]) and np.array_equal(host(bs.g_tex), ref[1]), f"replay {rep}"
+
+
+def test_autotune_strategies_give_identical_steps(small_batch):
+    """Both hard-rasterization strategies (triangle-parallel, pixel-parallel)
+    give bitwise the same step; the autotuner keeps the faster one."""
+    from paper_2204_01386_amd.pipeline import autotune
+    bs = _batched(small_batch)
+    outs = []
+    for hr in (0, 1):
+        bs.hard_raster = hr
+        bs.run()
+        torch.cuda.synchronize()
+        outs.append((host(bs.tri_id).copy(), host(bs.rgba()).copy(), host(bs.g_pos).copy(), host(bs.g_tex).copy()))
+    for a, b in zip(outs[0], outs[1]):
+        assert np.array_equal(a, b)
+    res = autotune(bs)
+    assert res["hard_raster"] in (0, 1) and bs.hard_raster == res["hard_raster"]
+    # a scene with large triangles on screen (few triangles, high resolution)
+    big = scenes.config4(seed=5, n=3, t_min=200, t_max=400, sizes=(512,), tex_size=64)
+    bs2 = _batched(big)
+    ref = host(bs2.g_pos).copy()
+    bs2.hard_raster = 1 - (bs2.hard_raster or 0)
+    bs2.run()
+    torch.cuda.synchronize()
+    assert np.array_equal(host(bs2.g_pos), ref)
