@@ -13,10 +13,63 @@
 
 #define IB_CH 16   // channels per pass of the per-triangle gather
 
-__global__ void k_interp(const float *__restrict__ attr, int Ba, int Va, int C,
-                         const int32_t *__restrict__ attr_tris, int T,
-                         const int32_t *__restrict__ tri_id, const float2 *__restrict__ bary,
-                         int64_t per_view, int64_t n, float *__restrict__ out) {
+// One lane per fragment; the block's outputs (256 fragments x C channels, a
+// contiguous range) are staged in LDS and written back with coalesced float4
+// stores.  CC = C at compile time (0: run time).
+template <int CC>
+__global__ void __launch_bounds__(256)
+    k_interp(const float *__restrict__ attr, int Ba, int Va, int C_, const int32_t *__restrict__ attr_tris,
+             int T, const int32_t *__restrict__ tri_id, const float2 *__restrict__ bary, int64_t per_view,
+             int64_t n, float *__restrict__ out) {
+    extern __shared__ float stage[];   // [256 * C]
+    const int C = CC > 0 ? CC : C_;
+    const int64_t o0 = (int64_t)blockIdx.x * 256;
+    const int64_t o = o0 + threadIdx.x;
+    float *y = stage + threadIdx.x * C;
+    if (o < n) {
+        int t = tri_id[o];
+        int v0 = -1, v1 = -1, v2 = -1;
+        if (t >= 0 && t < T) {
+            v0 = attr_tris[3 * (int64_t)t];
+            v1 = attr_tris[3 * (int64_t)t + 1];
+            v2 = attr_tris[3 * (int64_t)t + 2];
+        }
+        if (v0 < 0 || v0 >= Va || v1 < 0 || v1 >= Va || v2 < 0 || v2 >= Va) {
+            for (int c = 0; c < C; c++) y[c] = 0.0f;
+        } else {
+            int b = (int)(o / per_view);
+            const float *a = attr + (Ba == 1 ? 0 : (int64_t)b * Va * C);
+            float2 w = bary[o];
+            float w2 = 1.0f - w.x - w.y;
+            const float *a0 = a + (int64_t)v0 * C, *a1 = a + (int64_t)v1 * C, *a2 = a + (int64_t)v2 * C;
+            if constexpr (CC > 0) {
+#pragma unroll
+                for (int c = 0; c < CC; c++) y[c] = w.x * a0[c] + w.y * a1[c] + w2 * a2[c];
+            } else {
+                for (int c = 0; c < C; c++) y[c] = w.x * a0[c] + w.y * a1[c] + w2 * a2[c];
+            }
+        }
+    }
+    __syncthreads();
+    // the block's outputs are out[o0 * C, (o0 + cnt) * C)
+    const int64_t cnt = min((int64_t)256, n - o0);
+    const int64_t nf = cnt * C;
+    float *dst = out + o0 * C;
+    if (((o0 * C) & 3) == 0 && (((uintptr_t)out) & 15) == 0) {
+        const int64_t n4 = nf >> 2;
+        for (int64_t i = threadIdx.x; i < n4; i += 256)
+            reinterpret_cast<float4 *>(dst)[i] = reinterpret_cast<const float4 *>(stage)[i];
+        for (int64_t i = (n4 << 2) + threadIdx.x; i < nf; i += 256) dst[i] = stage[i];
+    } else {
+        for (int64_t i = threadIdx.x; i < nf; i += 256) dst[i] = stage[i];
+    }
+}
+
+// Wide attributes (C > 32): one lane per fragment writing its row directly.
+__global__ void k_interp_wide(const float *__restrict__ attr, int Ba, int Va, int C,
+                              const int32_t *__restrict__ attr_tris, int T, const int32_t *__restrict__ tri_id,
+                              const float2 *__restrict__ bary, int64_t per_view, int64_t n,
+                              float *__restrict__ out) {
     int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (o >= n) return;
     float *y = out + o * C;
@@ -61,9 +114,23 @@ extern "C" int dressi_interpolate(dressi_ctx *ctx, const float *attr, int Ba, in
     if (n == 0) return DRESSI_OK;
     if (!out) return dressi_fail(ctx, DRESSI_EINVAL, "interpolate: null out");
     hipStream_t st = (hipStream_t)stream;
-    DR_LAUNCH("k_interp", (k_interp), (int)((n + 255) / 256), 256, 0, st, attr, Ba, Va, C, attr_tris, T, tri_id,
-                                                     reinterpret_cast<const float2 *>(bary),
-                                                     (int64_t)K * H * W, n, out);
+    const int g = (int)((n + 255) / 256);
+    const size_t sh = sizeof(float) * 256 * (size_t)C;
+    const float2 *b2 = reinterpret_cast<const float2 *>(bary);
+    const int64_t pv = (int64_t)K * H * W;
+    switch (C) {
+    case 2: DR_LAUNCH("k_interp", (k_interp<2>), g, 256, sh, st, attr, Ba, Va, C, attr_tris, T, tri_id, b2, pv, n, out); break;
+    case 6: DR_LAUNCH("k_interp", (k_interp<6>), g, 256, sh, st, attr, Ba, Va, C, attr_tris, T, tri_id, b2, pv, n, out); break;
+    case 9: DR_LAUNCH("k_interp", (k_interp<9>), g, 256, sh, st, attr, Ba, Va, C, attr_tris, T, tri_id, b2, pv, n, out); break;
+    default:
+        if (C <= 32)
+            DR_LAUNCH("k_interp", (k_interp<0>), g, 256, sh, st, attr, Ba, Va, C, attr_tris, T, tri_id, b2, pv, n,
+                      out);
+        else
+            DR_LAUNCH("k_interp", (k_interp_wide), g, 256, 0, st, attr, Ba, Va, C, attr_tris, T, tri_id, b2, pv, n,
+                      out);
+        break;
+    }
     return dressi_launch_check(ctx, "interpolate");
 }
 
