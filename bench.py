@@ -411,10 +411,14 @@ def uneven_line(steps, prof_steps):
             "batched_vs_plain_speedup": round(m["plain_ms_per_step"] / m["ms_per_step"], 3),
             "step_alg_bytes": m["step_alg_bytes"],
             "step_hbm_frac": round(m["step_alg_bytes"] / (m["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-            "autotune": {"hard_raster": ["triangle-parallel", "pixel-parallel"][m["tuned"]["hard_raster"]],
-                         "raster_ms": {["triangle-parallel", "pixel-parallel"][k]: round(v, 4)
-                                       for k, v in m["tuned"]["ms"].items()}},
+            "autotune": {"hard_raster": _strategy_name(m["tuned"]["hard_raster"], m["tuned"]["hybrid_weight"]),
+                         "raster_ms": {_strategy_name(*k): round(v, 4) for k, v in m["tuned"]["ms"].items()}},
             "kernels": [{"kernel": k, "ms_per_step": round(v, 5)} for k, v in m["table"][:12]]}
+
+
+def _strategy_name(hr, w):
+    from paper_2204_01386_amd.pipeline import HARD_RASTER_NAMES
+    return HARD_RASTER_NAMES[hr] + (f" (weight {w}/16)" if hr == 2 else "")
 
 
 def main():

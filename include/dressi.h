@@ -95,10 +95,16 @@ int dressi_check_status(dressi_ctx *ctx, int64_t *needed, void *stream);
  *   too small a capacity is reported by dressi_check_status);
  * DRESSI_TUNE_HARD_RASTER: hard rasterization (r = 0) strategy, 0 =
  *   triangle-parallel per tile with LDS atomics (small triangles), 1 =
- *   pixel-parallel with per-pixel lists in registers (large triangles).
- *   Both select exactly the same layers. */
+ *   pixel-parallel with per-pixel lists in registers (large triangles), 2 =
+ *   chosen per tile and batch of 256 binned triangles from their on-tile
+ *   extents (K = 1; with K > 1 it acts as 1).  All select exactly the same
+ *   layers;
+ * DRESSI_TUNE_HYBRID_WEIGHT: for strategy 2, the cost of a pixel-parallel
+ *   triangle step relative to a triangle-parallel pixel step, in sixteenths
+ *   (1..1024, default 24). */
 #define DRESSI_TUNE_BIN_CAPACITY 1
 #define DRESSI_TUNE_HARD_RASTER 2
+#define DRESSI_TUNE_HYBRID_WEIGHT 3
 int dressi_tune(dressi_ctx *ctx, int key, int64_t value);
 
 /* Kernel timing for measurement: while on, every kernel launch of the library

@@ -122,8 +122,12 @@ extern "C" int dressi_tune(dressi_ctx *ctx, int key, int64_t value) {
         ctx->bin_capacity = value;   // 0 = automatic
         return DRESSI_OK;
     case DRESSI_TUNE_HARD_RASTER:
-        if (value != 0 && value != 1) return dressi_fail(ctx, DRESSI_EINVAL, "tune: hard raster is 0 or 1");
+        if (value < 0 || value > 2) return dressi_fail(ctx, DRESSI_EINVAL, "tune: hard raster is 0, 1 or 2");
         ctx->hard_raster = (int)value;
+        return DRESSI_OK;
+    case DRESSI_TUNE_HYBRID_WEIGHT:
+        if (value < 1 || value > 1024) return dressi_fail(ctx, DRESSI_EINVAL, "tune: hybrid weight is 1..1024");
+        ctx->hybrid_weight = (int)value;
         return DRESSI_OK;
     default:
         return dressi_fail(ctx, DRESSI_EINVAL, "tune: unknown key");

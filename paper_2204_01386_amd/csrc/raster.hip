@@ -355,6 +355,71 @@ __device__ __forceinline__ float rl_segmin_i(const int *qx, const int *qy, const
 
 // Merges the candidate fragment of triangle t at this lane's pixel.  MAYHARD
 // is false when no pixel centre of the wavefront can be inside the triangle.
+// One staged triangle (slot e of the batch) rasterized over its pixels in the
+// tile, hard fragments only, merged into the tile's per-pixel slots: the same
+// edge values (32-bit or exact double), depth and key as rl_merge.
+__device__ __forceinline__ void rl_tri_in_tile(int e, const int *sid, const int *sflag, const int2 *sbox,
+                                               const int4 *sxy0, const int2 *sxy1, const float4 *sz,
+                                               const int4 *sed, int tx, int ty,
+                                               unsigned long long *slot) {
+    const int fl = sflag[e];
+    if (!(fl & 1)) return;
+    const int2 bx = sbox[e];
+    const int x0 = max(bx.x & 0xffff, tx * DRESSI_TILE), x1 = min(bx.x >> 16, tx * DRESSI_TILE + DRESSI_TILE - 1);
+    const int y0 = max(bx.y & 0xffff, ty * DRESSI_TILE), y1 = min(bx.y >> 16, ty * DRESSI_TILE + DRESSI_TILE - 1);
+    if (x0 > x1 || y0 > y1) return;
+    const int t = sid[e];
+    const int4 q0 = sxy0[e];
+    const int2 q1 = sxy1[e];
+    const float4 z4 = sz[e];
+    TriSetup s;
+    s.X[0] = q0.x; s.X[1] = q0.y; s.X[2] = q0.z;
+    s.Y[0] = q0.w; s.Y[1] = q1.x; s.Y[2] = q1.y;
+    s.zn[0] = z4.x; s.zn[1] = z4.y; s.zn[2] = z4.z;
+    s.Af = z4.w;
+    s.meta = fl & 0xffff;
+    const bool own0 = (s.meta >> 1) & 1, own1 = (s.meta >> 2) & 1, own2 = (s.meta >> 3) & 1;
+    const bool small = fl >> 16;
+    int ex[3], ey[3];
+    {
+        const int4 ed = sed[e];
+        ex[0] = lo16(ed.x); ex[1] = lo16(ed.y); ex[2] = lo16(ed.z);
+        ey[0] = hi16(ed.x); ey[1] = hi16(ed.y); ey[2] = hi16(ed.z);
+    }
+    for (int y = y0; y <= y1; y++) {
+        const int py = DRESSI_SUBPIX * y + DRESSI_SUBPIX / 2;
+        for (int x = x0; x <= x1; x++) {
+            const int px = DRESSI_SUBPIX * x + DRESSI_SUBPIX / 2;
+            float z;
+            if (small) {
+                int E[3];
+#pragma unroll
+                for (int i = 0; i < 3; i++) {
+                    const int a = (i + 1) % 3;
+                    E[i] = __mul24(ex[i], py - s.Y[a]) - __mul24(ey[i], px - s.X[a]);
+                }
+                if (!((E[0] > 0 || (E[0] == 0 && own0)) && (E[1] > 0 || (E[1] == 0 && own1)) &&
+                      (E[2] > 0 || (E[2] == 0 && own2))))
+                    continue;
+                z = dr_depth(s, E);
+            } else {
+                double E[3];
+#pragma unroll
+                for (int i = 0; i < 3; i++) E[i] = dr_edge(s.X, s.Y, i, px, py);
+                if (!((E[0] > 0 || (E[0] == 0 && own0)) && (E[1] > 0 || (E[1] == 0 && own1)) &&
+                      (E[2] > 0 || (E[2] == 0 && own2))))
+                    continue;
+                z = dr_depth(s, E);
+            }
+            if (!(z > 0.0f && z < 1.0f)) continue;
+            const float key = 0.5f * z;
+            const int pp = (y - ty * DRESSI_TILE) * DRESSI_TILE + (x - tx * DRESSI_TILE);
+            const unsigned long long v = ((unsigned long long)__float_as_uint(key) << 32) | (unsigned)t;
+            atomicMin(&slot[pp], v);
+        }
+    }
+}
+
 template <int K, bool MAYHARD, typename TE, bool SOFT = true>
 __device__ __forceinline__ void rl_merge(const TriSetup &s, const TE *E, const float *el, int t, int px,
                                          int py, float dscale, float r, float reach, float *key, int *id,
@@ -424,12 +489,36 @@ __device__ __forceinline__ void rl_merge(const TriSetup &s, const TE *E, const f
     }
 }
 
-template <int K, bool SOFT>
+// HYB (hard, K = 1): every staged batch is rasterized either pixel-parallel
+// (the list walk below) or triangle-parallel (one lane per staged triangle,
+// walking its pixels in the tile and merging into a per-pixel LDS slot with a
+// 64-bit atomicMin, as k_raster does), whichever the batch's estimated cost
+// favours: the pixel-parallel walk costs about one iteration per (triangle,
+// wavefront strip it touches), the triangle-parallel one, per wavefront, the
+// largest pixel count of its lanes' triangles.  The slot and the register list
+// are merged at the end; both keep the smallest key and the smallest id at
+// that key, so the choice never changes the result.
+// hyb_w: the cost of a pixel-parallel triangle step relative to a
+// triangle-parallel pixel step, in sixteenths (a tuning knob).
+
+__device__ __forceinline__ int wave_sum_i(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ int wave_max_i(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+template <int K, bool SOFT, bool HYB = false>
 __global__ void __launch_bounds__(DRESSI_TILE_PIX) __attribute__((amdgpu_waves_per_eu(5)))
     k_raster_list(const TriSetup *__restrict__ setup, int32_t *__restrict__ counts,
                   const int32_t *__restrict__ bins, int cap, int T, int H, int W, int ntx, int nt,
                   float r, int32_t *__restrict__ tri_id, float2 *__restrict__ bary,
-                  float *__restrict__ dist) {
+                  float *__restrict__ dist, int hyb_w) {
     // staged triangles (structure of arrays)
     __shared__ int sid[RL_BATCH];       // triangle id
     __shared__ int sflag[RL_BATCH];     // meta | float-exact flag << 16
@@ -442,6 +531,11 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX) __attribute__((amdgpu_waves_p
     __shared__ float4 sz[RL_BATCH];     // zn0 zn1 zn2 Af
     __shared__ int4 sed[RL_BATCH];      // edge vectors (ex | ey << 16) of the 32-bit path
     __shared__ int4 slen[RL_BATCH];     // their squared lengths
+    // triangle-parallel batches (HYB): per-pixel slot and the batch costs,
+    // double-buffered by batch parity
+    __shared__ unsigned long long sslot[HYB ? DRESSI_TILE_PIX : 1];
+    __shared__ int scost[2][2];
+    static_assert(!HYB || (K == 1 && !SOFT), "the hybrid strategy is for one hard layer");
     const int bt = blockIdx.x;
     const int b = bt / nt, tile = bt - b * nt;
     const int tx = tile % ntx, ty = tile / ntx;
@@ -474,12 +568,21 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX) __attribute__((amdgpu_waves_p
     }
     int wmax_bits = __float_as_int(2.0f);   // bound on the strip's K-th keys (they only decrease)
     int gap_max = 0x3fffffff;               // soft-only triangles farther (pixels) than this are culled
+    if (HYB) {
+        sslot[p] = RS_EMPTY;
+        if (p < 4) scost[p >> 1][p & 1] = 0;
+    }
 
     for (int walk = 0; walk < (SOFT ? 3 : 1); walk++) {   // hard only: covering triangles
         for (int c0 = 0; c0 < nbin; c0 += RL_BATCH) {
             const int n = min(RL_BATCH, nbin - c0);
+            const int par = (c0 / RL_BATCH) & 1;
+            bool use_tp = false;
             if (walk == 0 || nbin > RL_BATCH) {   // a single batch stays staged
                 __syncthreads();
+                // the other parity's costs were read before this barrier
+                if (HYB && p < 2) scost[par ^ 1][p] = 0;
+                int tp_pix = 0, pp_steps = 0;
                 if (p < n) {
                     const int t = bin[c0 + p];
                     const TriSetup s = sv[t];
@@ -509,8 +612,31 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX) __attribute__((amdgpu_waves_p
                     sxy0[p] = make_int4(s.X[0], s.X[1], s.X[2], s.Y[0]);
                     sxy1[p] = make_int2(s.Y[1], s.Y[2]);
                     sz[p] = make_float4(s.zn[0], s.zn[1], s.zn[2], s.Af);
+                    if (HYB && (s.meta & 1)) {
+                        const int bx0 = max(s.box0 & 0xffff, wx0), bx1 = min(s.box0 >> 16, wx1);
+                        const int by0 = max(s.box1 & 0xffff, ty * DRESSI_TILE);
+                        const int by1 = min(s.box1 >> 16, ty * DRESSI_TILE + DRESSI_TILE - 1);
+                        if (bx0 <= bx1 && by0 <= by1) {
+                            tp_pix = (bx1 - bx0 + 1) * (by1 - by0 + 1);
+                            const int strip = 64 / DRESSI_TILE;   // rows per wavefront
+                            pp_steps = (by1 - ty * DRESSI_TILE) / strip - (by0 - ty * DRESSI_TILE) / strip + 1;
+                        }
+                    }
+                }
+                if (HYB) {
+                    tp_pix = wave_max_i(tp_pix);
+                    pp_steps = wave_sum_i(pp_steps);
+                    if (lane == 0) {
+                        atomicAdd(&scost[par][0], tp_pix);
+                        atomicAdd(&scost[par][1], pp_steps);
+                    }
                 }
                 __syncthreads();
+            }
+            if (HYB) use_tp = 16 * scost[par][0] < hyb_w * scost[par][1];
+            if (HYB && use_tp) {
+                if (p < n) rl_tri_in_tile(p, sid, sflag, sbox, sxy0, sxy1, sz, sed, tx, ty, sslot);
+                continue;
             }
             for (int c = 0; c < n; c += 64) {
                 // 64 triangles tested at once, one per lane
@@ -588,6 +714,17 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX) __attribute__((amdgpu_waves_p
         }
     }
     __syncthreads();
+    if (HYB) {
+        const unsigned long long v = sslot[p];
+        if (v != RS_EMPTY) {
+            const float k2 = __uint_as_float((unsigned)(v >> 32));
+            const int t2 = (int)(v & 0xffffffffu);
+            if (k2 < key[0] || (k2 == key[0] && t2 < id[0])) {
+                key[0] = k2;
+                id[0] = t2;
+            }
+        }
+    }
     if (p == 0) counts[bt] = 0;   // every lane has read it before the first barrier
     resolve_store<K, SOFT>(sv, key, id, b, x, y, px, py, H, W, dscale, tri_id, bary, dist);
 }
@@ -597,15 +734,18 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX) __attribute__((amdgpu_waves_p
 // with LDS atomics (small triangles) or pixel-parallel with register lists
 // (large triangles); dressi_tune picks one per context.
 template <int K>
-static void launch_raster_k(bool soft, int hard_pix, dim3 g, hipStream_t st, const TriSetup *setup,
+static void launch_raster_k(bool soft, int hard_pix, int hyb_w, dim3 g, hipStream_t st, const TriSetup *setup,
                             int32_t *counts, const int32_t *bins, int cap, int T, int H, int W, int ntx, int nt,
                             float r, int32_t *tid, float2 *bary, float *dist) {
     if (soft)
         DR_LAUNCH("k_raster_list", (k_raster_list<K, true>), g, DRESSI_TILE_PIX, 0, st, setup, counts, bins, cap,
-                  T, H, W, ntx, nt, r, tid, bary, dist);
+                  T, H, W, ntx, nt, r, tid, bary, dist, 0);
+    else if (hard_pix == 2 && K == 1)
+        DR_LAUNCH("k_raster_list", (k_raster_list<1, false, true>), g, DRESSI_TILE_PIX, 0, st, setup, counts,
+                  bins, cap, T, H, W, ntx, nt, r, tid, bary, dist, hyb_w);
     else if (hard_pix)
         DR_LAUNCH("k_raster_list", (k_raster_list<K, false>), g, DRESSI_TILE_PIX, 0, st, setup, counts, bins,
-                  cap, T, H, W, ntx, nt, r, tid, bary, dist);
+                  cap, T, H, W, ntx, nt, r, tid, bary, dist, 0);
     else
         DR_LAUNCH("k_raster", (k_raster<K, false>), g, DRESSI_TILE_PIX, 0, st, setup, counts, bins, cap, T, H,
                   W, ntx, nt, r, tid, bary, dist);
@@ -681,13 +821,13 @@ static int rasterize_impl(dressi_ctx *ctx, const float *pos_clip, const int32_t 
                   nt, cap, setup, counts, bins, reinterpret_cast<unsigned long long *>(ctx->status));
     dim3 g((unsigned)(B * nt));
     float2 *b2 = reinterpret_cast<float2 *>(bary);
-    const int hp = ctx->hard_raster;
+    const int hp = ctx->hard_raster, hw = ctx->hybrid_weight;
     switch (K) {
-    case 1: launch_raster_k<1>(soft, hp, g, st, setup, counts, bins, cap, T, H, W, ntx, nt, r, tri_id, b2, dist); break;
-    case 2: launch_raster_k<2>(soft, hp, g, st, setup, counts, bins, cap, T, H, W, ntx, nt, r, tri_id, b2, dist); break;
-    case 3: launch_raster_k<3>(soft, hp, g, st, setup, counts, bins, cap, T, H, W, ntx, nt, r, tri_id, b2, dist); break;
-    case 4: launch_raster_k<4>(soft, hp, g, st, setup, counts, bins, cap, T, H, W, ntx, nt, r, tri_id, b2, dist); break;
-    default: launch_raster_k<5>(soft, hp, g, st, setup, counts, bins, cap, T, H, W, ntx, nt, r, tri_id, b2, dist); break;
+    case 1: launch_raster_k<1>(soft, hp, hw, g, st, setup, counts, bins, cap, T, H, W, ntx, nt, r, tri_id, b2, dist); break;
+    case 2: launch_raster_k<2>(soft, hp, hw, g, st, setup, counts, bins, cap, T, H, W, ntx, nt, r, tri_id, b2, dist); break;
+    case 3: launch_raster_k<3>(soft, hp, hw, g, st, setup, counts, bins, cap, T, H, W, ntx, nt, r, tri_id, b2, dist); break;
+    case 4: launch_raster_k<4>(soft, hp, hw, g, st, setup, counts, bins, cap, T, H, W, ntx, nt, r, tri_id, b2, dist); break;
+    default: launch_raster_k<5>(soft, hp, hw, g, st, setup, counts, bins, cap, T, H, W, ntx, nt, r, tri_id, b2, dist); break;
     }
     return dressi_launch_check(ctx, "rasterize");
 }
@@ -964,7 +1104,9 @@ __device__ __forceinline__ void frag_range(const FragLists &fl, int64_t bt, int6
 // ---------------------------------------------------------------------------
 
 // gradient of one fragment: out[corner*3 + {0,1,2}] = d/dx_screen, d/dy_screen,
-// d/dw (direct) of that corner, original corner order
+// d/dw (direct) of that corner, original corner order.  Every array index is a
+// compile-time constant (selects, not indexing by the corner order), so the
+// whole record stays in registers.
 __device__ __forceinline__ void rast_frag_grad(const TriSetup &s, int x, int y, float2 g2, float gdist,
                                                bool want_dist, int W, float *out) {
     const int px = DRESSI_SUBPIX * x + DRESSI_SUBPIX / 2, py = DRESSI_SUBPIX * y + DRESSI_SUBPIX / 2;
@@ -977,29 +1119,31 @@ __device__ __forceinline__ void rast_frag_grad(const TriSetup &s, int x, int y, 
         in = in && (E[i] > 0 || (E[i] == 0 && own));
     }
     const bool swapped = dr_corner(s.meta, 1) == 2;
-    // the barycentric chain runs in double (see the forward)
-    const double A2d = (double)s.Af;
-    const double A = A2d * (1.0 / 65536.0);
-    double l[3], q[3];
+    // the barycentric chain runs in double (see the forward); reciprocals are
+    // taken once per fragment
+    const double iA2 = 1.0 / (double)s.Af;
+    // d(edge)/d(screen) scale: 1/256 per sub-pixel unit over the area in pixels
+    const double sA = 256.0 * iA2;
+    double l[3], q[3], iw[3];
 #pragma unroll
     for (int i = 0; i < 3; i++) {
-        l[i] = (double)E[i] / A2d;
-        q[i] = l[i] / (double)s.w[i];
+        iw[i] = 1.0 / (double)s.w[i];
+        l[i] = E[i] * iA2;
+        q[i] = l[i] * iw[i];
     }
-    double Q = q[0] + q[1] + q[2];
+    const double iQ = 1.0 / (q[0] + q[1] + q[2]);
     // gradient on the normalised-order barycentrics (original corner 2 has none)
     double gb[3] = {g2.x, swapped ? 0.0 : (double)g2.y, swapped ? (double)g2.y : 0.0};
-    double sb = (gb[0] * q[0] + gb[1] * q[1] + gb[2] * q[2]) / Q;
+    double sb = (gb[0] * q[0] + gb[1] * q[1] + gb[2] * q[2]) * iQ;
     double Gx = 0.0, Gy = 0.0, gw[3];
 #pragma unroll
     for (int i = 0; i < 3; i++) {
         int a = (i + 1) % 3, c = (i + 2) % 3;
-        double wi = (double)s.w[i];
-        double gq = (gb[i] - sb) / Q;
-        double gl = gq / wi;
-        gw[i] = -gq * l[i] / (wi * wi);
-        Gx += gl * (-((double)s.Y[c] - (double)s.Y[a]) * (1.0 / 256.0) / A);
-        Gy += gl * (((double)s.X[c] - (double)s.X[a]) * (1.0 / 256.0) / A);
+        double gq = (gb[i] - sb) * iQ;
+        double gl = gq * iw[i];
+        gw[i] = -gq * l[i] * iw[i] * iw[i];
+        Gx -= gl * ((double)s.Y[c] - (double)s.Y[a]) * sA;
+        Gy += gl * ((double)s.X[c] - (double)s.X[a]) * sA;
     }
     float gsx[3], gsy[3];
 #pragma unroll
@@ -1010,9 +1154,13 @@ __device__ __forceinline__ void rast_frag_grad(const TriSetup &s, int x, int y, 
     if (want_dist && gdist != 0.0f) {
         int ne;
         dr_distnorm(s.X, s.Y, px, py, E, (float)W * 256.0f, ne);
-        int a = (ne + 1) % 3, c = (ne + 2) % 3;
-        float sxa = (float)s.X[a] * (1.0f / 256.0f), sya = (float)s.Y[a] * (1.0f / 256.0f);
-        float sxc = (float)s.X[c] * (1.0f / 256.0f), syc = (float)s.Y[c] * (1.0f / 256.0f);
+        // the nearest edge runs from corner a = ne+1 to corner c = ne+2 (mod 3)
+        const int Xa = ne == 0 ? s.X[1] : (ne == 1 ? s.X[2] : s.X[0]);
+        const int Ya = ne == 0 ? s.Y[1] : (ne == 1 ? s.Y[2] : s.Y[0]);
+        const int Xc = ne == 0 ? s.X[2] : (ne == 1 ? s.X[0] : s.X[1]);
+        const int Yc = ne == 0 ? s.Y[2] : (ne == 1 ? s.Y[0] : s.Y[1]);
+        float sxa = (float)Xa * (1.0f / 256.0f), sya = (float)Ya * (1.0f / 256.0f);
+        float sxc = (float)Xc * (1.0f / 256.0f), syc = (float)Yc * (1.0f / 256.0f);
         float Px = (float)x + 0.5f, Py = (float)y + 0.5f;
         float ex = sxc - sxa, ey = syc - sya;
         float tt = ((Px - sxa) * ex + (Py - sya) * ey) / (ex * ex + ey * ey);
@@ -1022,23 +1170,29 @@ __device__ __forceinline__ void rast_frag_grad(const TriSetup &s, int x, int y, 
         float d = sqrtf(dx * dx + dy * dy);
         if (d > 0.0f) {
             float sg = (in ? gdist : -gdist) / ((float)W * d);
-            gsx[a] -= sg * (1.0f - tt) * dx;
-            gsy[a] -= sg * (1.0f - tt) * dy;
-            gsx[c] -= sg * tt * dx;
-            gsy[c] -= sg * tt * dy;
+            float ga = sg * (1.0f - tt), gc = sg * tt;
+#pragma unroll
+            for (int i = 0; i < 3; i++) {
+                const bool is_a = i == (ne + 1) % 3, is_c = i == (ne + 2) % 3;
+                gsx[i] -= is_a ? ga * dx : (is_c ? gc * dx : 0.0f);
+                gsy[i] -= is_a ? ga * dy : (is_c ? gc * dy : 0.0f);
+            }
         }
     }
-#pragma unroll
-    for (int i = 0; i < 3; i++) {
-        int corner = dr_corner(s.meta, i);
-        out[corner * 3 + 0] = gsx[i];
-        out[corner * 3 + 1] = gsy[i];
-        out[corner * 3 + 2] = (float)gw[i];
-    }
+    // normalised order is (0, 1, 2), or (0, 2, 1) when the winding was flipped
+    out[0] = gsx[0];
+    out[1] = gsy[0];
+    out[2] = (float)gw[0];
+    out[3] = swapped ? gsx[2] : gsx[1];
+    out[4] = swapped ? gsy[2] : gsy[1];
+    out[5] = (float)(swapped ? gw[2] : gw[1]);
+    out[6] = swapped ? gsx[1] : gsx[2];
+    out[7] = swapped ? gsy[1] : gsy[2];
+    out[8] = (float)(swapped ? gw[1] : gw[2]);
 }
 
 __global__ void __launch_bounds__(DRESSI_TILE_PIX)
-    k_rast_bwd_tile(const float4 *__restrict__ pos_clip, const int32_t *__restrict__ tris, Viewports vp, int V,
+    __attribute__((amdgpu_waves_per_eu(5))) k_rast_bwd_tile(const float4 *__restrict__ pos_clip, const int32_t *__restrict__ tris, Viewports vp, int V,
                     int T, int H, int W, int K, int cull, int margin, const int32_t *__restrict__ tri_id,
                     FragLists fl, int ntx, int nt, const float2 *__restrict__ grad_bary,
                     const float *__restrict__ grad_dist, float *__restrict__ partial) {

@@ -25,6 +25,11 @@ from .scenes import Scene
 
 _lib = Bd._lib
 
+# per-tile hard rasterization: cost of a pixel-parallel triangle step over a
+# triangle-parallel pixel step, in sixteenths; the autotuner tries these
+HYBRID_WEIGHT_DEFAULT = 24
+HYBRID_WEIGHTS = (12, 16, 24, 40)
+
 
 def _p(t):
     return None if t is None else C.c_void_p(t.data_ptr())
@@ -149,11 +154,13 @@ class Step:
         self._fin = self._frag_in()
         self._fin_dir = self._frag_in(with_env=False)
         self.hard_raster = None     # rasterization strategy chosen by autotune() (None: triangle-parallel)
+        self.hybrid_weight = HYBRID_WEIGHT_DEFAULT
         self._calibrate_bins()
 
     def _raster(self):
         h, st = self.ctx.handle, self._s()
         self.ctx.tune(Bd.TUNE_HARD_RASTER, self.hard_raster or 0)
+        self.ctx.tune(Bd.TUNE_HYBRID_WEIGHT, self.hybrid_weight)
         self._chk(_lib.dressi_transform(h, _p(self.pos), _p(self.mvp), self.B, self.V, _p(self.pos_clip), st),
                   "transform")
         self._chk(_lib.dressi_rasterize(h, _p(self.pos_clip), _p(self.tris), self.B, self.V, self.T, self.H,
@@ -438,6 +445,7 @@ class BatchStep:
         fi.tri_eye = C.c_void_p(self.tri_view.data_ptr())
         self._fin = fi
         self.hard_raster = None
+        self.hybrid_weight = HYBRID_WEIGHT_DEFAULT
         self._calibrate_bins()
 
     def _s(self):
@@ -450,6 +458,7 @@ class BatchStep:
     def _raster(self):
         h, st = self.ctx.handle, self._s()
         self.ctx.tune(Bd.TUNE_HARD_RASTER, self.hard_raster or 0)
+        self.ctx.tune(Bd.TUNE_HYBRID_WEIGHT, self.hybrid_weight)
         self._chk(_lib.dressi_transform_batched(h, _p(self.pos), _p(self.vert_view), _p(self.mvp), self.V,
                                                 _p(self.pos_clip), st), "transform_batched")
         self._chk(_lib.dressi_rasterize_batched(h, _p(self.pos_clip), _p(self.tris), _p(self.tri_view),
@@ -553,22 +562,29 @@ def make_batch_target(scenes_list, device="cuda") -> BatchStep:
 # ---------------------------------------------------------------------------
 # autotuning
 # ---------------------------------------------------------------------------
+HARD_RASTER_NAMES = {None: "triangle-parallel", 0: "triangle-parallel", 1: "pixel-parallel", 2: "per-tile"}
 def autotune(step, reps: int = 5) -> dict:
-    """Picks the hard-rasterization strategy (triangle-parallel or
-    pixel-parallel tiles) and the tile-bin capacity for this step's own
-    geometry by timing each candidate's transform + rasterization on the
-    device, after checking that it selects exactly the same layers as the
-    first candidate (it must: the choice changes speed only).  The choice is
-    stored on the step and applied at every later rasterization, so it is
-    also what a captured graph records.  Soft rasterization (r > 0) has one
-    strategy; only its bin capacity is tuned."""
+    """Picks the hard-rasterization strategy (triangle-parallel tiles,
+    pixel-parallel tiles, or a choice per tile and triangle batch with one of
+    a few cost weights) and the tile-bin capacity for this step's own geometry
+    by timing each candidate's transform + rasterization on the device, after
+    checking that it selects exactly the same layers as the first candidate
+    (it must: the choice changes speed only).  The choice is stored on the
+    step and applied at every later rasterization, so it is also what a
+    captured graph records.  Soft rasterization (r > 0) has one strategy; only
+    its bin capacity is tuned."""
     ctx = step.ctx
-    strategies = [0, 1] if getattr(step, "r", 0.0) == 0 else [None]
+    if getattr(step, "r", 0.0) != 0:
+        cands = [(None, HYBRID_WEIGHT_DEFAULT)]
+    else:
+        cands = [(0, HYBRID_WEIGHT_DEFAULT), (1, HYBRID_WEIGHT_DEFAULT)]
+        if getattr(step, "K", 1) == 1:
+            cands += [(2, w) for w in HYBRID_WEIGHTS]
     need = 0
     results = {}
     ref = None
-    for hr in strategies:
-        step.hard_raster = hr
+    for hr, w in cands:
+        step.hard_raster, step.hybrid_weight = hr, w
         step._raster()
         torch.cuda.synchronize()
         need = max(need, ctx.check_status())
@@ -576,16 +592,16 @@ def autotune(step, reps: int = 5) -> dict:
         if ref is None:
             ref = tid
         elif not torch.equal(ref, tid):
-            raise RuntimeError(f"rasterization strategy {hr} selects different layers")
+            raise RuntimeError(f"rasterization strategy {hr} (weight {w}) selects different layers")
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
         for _ in range(reps):
             step._raster()
         e1.record()
         torch.cuda.synchronize()
-        results[hr] = e0.elapsed_time(e1) / reps
+        results[(hr, w)] = e0.elapsed_time(e1) / reps
     best = min(results, key=results.get)
-    step.hard_raster = best
+    step.hard_raster, step.hybrid_weight = best
     # bin capacity: the smallest power of two above 5/4 of the fullest tile
     cap = 0
     if need > 0:
@@ -593,4 +609,4 @@ def autotune(step, reps: int = 5) -> dict:
         while cap < need * 5 // 4:
             cap <<= 1
         ctx.reserve(0, cap)
-    return {"hard_raster": best, "ms": results, "bin_capacity": cap}
+    return {"hard_raster": best[0], "hybrid_weight": best[1], "ms": results, "bin_capacity": cap}

@@ -182,6 +182,32 @@ def test_raster_config3_views_full_size(B):
     check_raster(B, pc, s.tris, 512, 512, 3, 0.01, seed=8)
 
 
+@pytest.mark.parametrize("hr,w", [(1, 40), (2, 1), (2, 40), (2, 1024)])
+def test_raster_hard_strategies(B, hr, w):
+    """Every hard-rasterization strategy selects exactly the oracle's layers:
+    pixel-parallel, and per tile and triangle batch (with weights that force
+    either side everywhere and the default mix).  Large on-screen triangles
+    (a coarse tiling, the K = 2 multi-layer case), small ones (the 81,920
+    triangle sphere) and adversarial ones (shared edges, duplicates)."""
+    ctx = B.context()
+    ctx.tune(B.TUNE_HARD_RASTER, hr)
+    ctx.tune(B.TUNE_HYBRID_WEIGHT, w)
+    try:
+        pc, tris = tiling(48, 40, 23, True)
+        tid = check_raster(B, pc, tris, 48, 40, 1, 0.0, bwd=False)
+        assert (tid[0, 0] >= 0).all()
+        pc, tris = random_tiny(11, T=40, H=70, W=53)
+        check_raster(B, pc, tris, 70, 53, 1, 0.0, seed=11)
+        check_raster(B, pc, tris, 70, 53, 2, 0.0, seed=12, bwd=False)
+        s = scenes.config1()
+        check_raster(B, to_clip(s.pos, s.mvp), s.tris, 128, 128, 1, 0.0, bwd=False)
+        s = scenes.config2()
+        check_raster(B, to_clip(s.pos, s.mvp), s.tris, 512, 512, 1, 0.0, bwd=False)
+    finally:
+        ctx.tune(B.TUNE_HARD_RASTER, 0)
+        ctx.tune(B.TUNE_HYBRID_WEIGHT, 24)
+
+
 def test_raster_empty_inputs(B):
     pc = np.zeros((1, 3, 4), np.float32)
     tris = np.zeros((0, 3), np.int32)
