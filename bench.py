@@ -193,12 +193,12 @@ def kernel_bytes(name, z: Shapes):
         return N * 12 + N * Cv * 4 + V * Cv * 4 + T * 12 + (N * 8 if z.Ct else 0) + N * 8
     if name == "k_interp_bwd_bary":
         return z.Vuv * 8 + T * 12 + N * 12 + N * 8 + N * 8
-    if name == "k_interp_vertex_gather":
+    if name == "k_interp_bwd_vertex":
         return z.adj + V * Cv * 4
     if name == "k_rast_bwd_tile":
         return B * V * 16 + T * 12 + N * (4 + 8 + d)
-    if name == "k_vertex_gather_pos":
-        return z.adj + B * V * 16
+    if name == "k_rast_bwd_vertex":
+        return z.adj + B * V * 16 + B * V * 16
     if name == "k_fragsort":
         return N * 4
     if name == "k_transform":
@@ -224,7 +224,7 @@ def measure(scene, steps, warmup, prof_steps, plain_steps_min=10):
     import torch
 
     from paper_2204_01386_amd import binding as Bd
-    from paper_2204_01386_amd.pipeline import Step, make_target
+    from paper_2204_01386_amd.pipeline import Step, autotune, make_target
 
     B = scene.mvp.shape[0]
     tgt = make_target(scene)
@@ -237,6 +237,9 @@ def measure(scene, steps, warmup, prof_steps, plain_steps_min=10):
     torch.cuda.synchronize()
     if ctx.check_status() != 0:
         raise SystemExit("tile-bin capacity overflow during warm-up")
+    tuned = autotune(st)
+    st.run()
+    torch.cuda.synchronize()
     graph = torch.cuda.CUDAGraph()
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
@@ -263,7 +266,7 @@ def measure(scene, steps, warmup, prof_steps, plain_steps_min=10):
     ms_batched = e0.elapsed_time(e1) / steps
     if ctx.check_status() != 0:
         raise SystemExit("tile-bin capacity overflow in the timed region")
-    res = {"ms_per_step": ms_batched, "wall_s_timed": t_wall, "graph": graph, "step": st}
+    res = {"ms_per_step": ms_batched, "wall_s_timed": t_wall, "graph": graph, "step": st, "tuned": tuned}
     if prof_steps < 0:
         return res
 
@@ -274,6 +277,7 @@ def measure(scene, steps, warmup, prof_steps, plain_steps_min=10):
         plain_steps = [Step(scene, views=slice(v, v + 1), target=None) for v in range(B)]
         for v, ps in enumerate(plain_steps):
             ps.target.copy_(tgt.rgba()[v:v + 1])
+            ps.hard_raster, ps.hybrid_weight = st.hard_raster, st.hybrid_weight
     for _ in range(3):
         for ps in plain_steps:
             ps.run()
@@ -455,6 +459,8 @@ def main():
                     "launches_per_step": c, "alg_bytes": kernel_bytes(k, z)} for k, a, b, c in table]
     ms_plain = m["plain_ms_per_step"]
     launch_rows = [{"launch": k, "ms": round(a, 5)} for k, a in m["launches"][:16]]
+    tuned = {"hard_raster": _strategy_name(m["tuned"]["hard_raster"], m["tuned"]["hybrid_weight"]),
+             "raster_ms": {_strategy_name(*k): round(v, 4) for k, v in m["tuned"]["ms"].items()}}
     del m
 
     # ---- the 16-view batched configuration beside its per-view form -------
@@ -521,6 +527,7 @@ def main():
         "plain": {"ms_per_step": round(ms_plain, 5),
                   "value": round(pix / (ms_plain * 1e-3) / 1e6, 3), "unit": "Mpix/s"},
         "batched_vs_plain_speedup": round(ms_plain / ms_batched, 3),
+        "autotune": tuned,
         "step_alg_bytes": step_bytes,
         "step_hbm_frac": round(step_bytes / (ms_batched * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "roofline": {"bound": "hbm", "kernel": dom[0],

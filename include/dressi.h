@@ -187,8 +187,8 @@ int dressi_rasterize_batched_bwd(dressi_ctx *ctx, const float *pos_clip, const i
  *
  * dressi_fragment_index: from tri_id [B,K,H,W] (triangles < T), writes into
  * `index` (dressi_fragment_index_bytes(...) bytes, caller-owned, opaque) the
- * fragments of every 16x16 screen tile sorted by triangle id (an LDS bitonic
- * sort per tile) and, per (view, triangle), the list of tiles holding its
+ * fragments of every 16x16 screen tile sorted by triangle id (per tile:
+ * wavefront sorts of 64 keys merged by rank in LDS) and, per (view, triangle), the list of tiles holding its
  * fragments.  Build once per rasterization and pass it to rasterize_bwd and
  * interpolate_bwd.
  * ------------------------------------------------------------------------- */
@@ -212,7 +212,9 @@ int dressi_interpolate(dressi_ctx *ctx, const float *attr, int Ba, int Va, int C
  * [B,K,H,W,2]; either may be NULL.  grad_bary_in (NULL = 0) is added to
  * grad_bary, so several interpolations of one rasterization can chain their
  * barycentric gradients.  frag_index / adj (of attr_tris over Va vertices):
- * as for dressi_rasterize_bwd, NULL = built internally.  Deterministic. */
+ * as for dressi_rasterize_bwd, NULL = built internally.  Deterministic.
+ * With grad_attr, ((C + 2) | 1) * K must be at most 160 (a tile's fragments are
+ * staged in at most 160 KiB of LDS); larger requests return DRESSI_EINVAL. */
 int dressi_interpolate_bwd(dressi_ctx *ctx, const float *attr, int Ba, int Va, int C,
                            const int32_t *attr_tris, int T, const int32_t *tri_id,
                            const float *bary, int B, int K, int H, int W,

@@ -3,10 +3,10 @@
 // Forward: one lane per (pixel, layer) fragment; memory bound.
 // Backward: grad_bary is elementwise; grad_attr is a deterministic gather:
 // fragments are sorted per tile by triangle id (shared with the rasterizer
-// backward), each (view, triangle) walks its fragments through the
-// triangle->tile transpose and accumulates b_i * g for its three corners in
-// registers, then one thread per attribute vertex sums its corners in
-// ascending order.  No float atomics.
+// backward) and each tile sums b_i * g per triangle into one record; then per
+// attribute vertex and channel, every corner's records are summed in tile
+// order (through the triangle->tile transpose) and the corners in ascending
+// order.  No float atomics.
 #include "dressi_internal.h"
 
 #include <algorithm>
@@ -167,23 +167,46 @@ __global__ void k_interp_bwd_bary(const float *__restrict__ attr, int Ba, int Va
     grad_bary[o] = make_float2(acc.x + g0, acc.y + g1);
 }
 
+// Row of C floats; CC = C at compile time (0: run time), 8-byte aligned rows
+// with an even CC are read in pairs.
+template <int CC>
+__device__ __forceinline__ void ld_row(const float *src, float *v, int C) {
+    if constexpr (CC > 0 && (CC & 1) == 0) {
+#pragma unroll
+        for (int c = 0; c < CC; c += 2) {
+            const float2 q = *reinterpret_cast<const float2 *>(src + c);
+            v[c] = q.x;
+            v[c + 1] = q.y;
+        }
+    } else if constexpr (CC > 0) {
+#pragma unroll
+        for (int c = 0; c < CC; c++) v[c] = src[c];
+    }
+}
+
+// LDS row stride of a fragment: odd, so that lanes writing consecutive rows
+// fall in distinct banks
+__host__ __device__ static inline int ib_stride(int C) { return (C + 2) | 1; }
+
 // per tile: every fragment's (b0, b1, g_0..g_{C-1}) in LDS; each triangle's
 // fragments (consecutive in the tile's sorted list) are summed into one
 // record of b_i g_c for its three corners.  Also writes grad_bary.
+template <int CC>
 __global__ void __launch_bounds__(DRESSI_TILE_PIX)
     k_interp_bwd_tile(const float *__restrict__ attr, int Ba, int Va, int C,
                       const int32_t *__restrict__ attr_tris, int T, const int32_t *__restrict__ tri_id,
                       const float2 *__restrict__ bary, int K, int H, int W, int ntx, int nt, FragLists fl,
                       const float *__restrict__ grad_out, const float2 *__restrict__ gb_in,
                       float2 *__restrict__ grad_bary, float *__restrict__ partial) {
-    extern __shared__ float vals[];   // [K*256][C+2]
+    extern __shared__ float vals[];   // [K*256][ib_stride(C)]
+    if (CC > 0) C = CC;
     const int bt = blockIdx.x;
     const int b = bt / nt, tile = bt - b * nt;
     const int tx = tile % ntx, ty = tile / ntx;
     const int p = threadIdx.x;
     const int x = tx * DRESSI_TILE + (p & (DRESSI_TILE - 1));
     const int y = ty * DRESSI_TILE + p / DRESSI_TILE;
-    const int S = C + 2;
+    const int S = ib_stride(C);
     const float *ab = attr + (Ba == 1 ? 0 : (int64_t)b * Va * C);
     if (x < W && y < H) {
         for (int k = 0; k < K; k++) {
@@ -205,11 +228,25 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX)
                 dst[1] = w.y;
                 const float *a0 = ab + (int64_t)v0 * C, *a1 = ab + (int64_t)v1 * C, *a2 = ab + (int64_t)v2 * C;
                 float g0 = 0.0f, g1 = 0.0f;
-                for (int c = 0; c < C; c++) {
-                    float gc = g[c];
-                    dst[2 + c] = gc;
-                    g0 += gc * (a0[c] - a2[c]);
-                    g1 += gc * (a1[c] - a2[c]);
+                if constexpr (CC > 0) {
+                    float gv[CC], r0[CC], r1[CC], r2[CC];
+                    ld_row<CC>(g, gv, C);
+                    ld_row<CC>(a0, r0, C);
+                    ld_row<CC>(a1, r1, C);
+                    ld_row<CC>(a2, r2, C);
+#pragma unroll
+                    for (int c = 0; c < CC; c++) {
+                        dst[2 + c] = gv[c];
+                        g0 += gv[c] * (r0[c] - r2[c]);
+                        g1 += gv[c] * (r1[c] - r2[c]);
+                    }
+                } else {
+                    for (int c = 0; c < C; c++) {
+                        float gc = g[c];
+                        dst[2 + c] = gc;
+                        g0 += gc * (a0[c] - a2[c]);
+                        g1 += gc * (a1[c] - a2[c]);
+                    }
                 }
                 acc.x += g0;
                 acc.y += g1;
@@ -258,54 +295,41 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX)
     }
 }
 
-// per (shared or per-view, triangle): its records summed over views and tiles
-__global__ void k_interp_bwd_sum(int B, int Ba, int T, int K, int C, TriTiles tt,
-                                 const float *__restrict__ partial, float *__restrict__ corner_grad) {
-    int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int chunk = blockIdx.y;
-    const int c0 = chunk * IB_CH;
-    if (gid >= (int64_t)Ba * T) return;
-    int ba = (int)(gid / T), t = (int)(gid - (int64_t)ba * T);
-    float acc[3][IB_CH];
-#pragma unroll
-    for (int i = 0; i < 3; i++)
-#pragma unroll
-        for (int c = 0; c < IB_CH; c++) acc[i][c] = 0.0f;
-    int b0 = (Ba == 1) ? 0 : ba, b1 = (Ba == 1) ? B : ba + 1;
-    for (int b = b0; b < b1; b++) {
-        int64_t key = (int64_t)b * T + t;
-        for (int e = tt.offsets[key]; e < tt.offsets[key + 1]; e++) {
-            int2 ent = tt.entries[e];
-            const float *v = partial + ((int64_t)ent.x * DRESSI_TILE_PIX * K + ent.y) * 3 * C;
-#pragma unroll
-            for (int i = 0; i < 3; i++)
-#pragma unroll
-                for (int c = 0; c < IB_CH; c++)
-                    if (c0 + c < C) acc[i][c] += v[i * C + c0 + c];
+// Four lanes per (shared or per-view attribute set, vertex, channel); lane j
+// takes the vertex's corners j, j+4, ... in ascending order, sums each
+// corner's tile records over views and tiles in order and adds the corner
+// sum to its own; the four lane sums are combined in a fixed butterfly order.
+#define IBV_LANES 4
+__global__ void k_interp_bwd_vertex(int B, int Ba, int Va, int T, int K, int C, TriTiles tt,
+                                    const float *__restrict__ partial, Adjacency adj,
+                                    float *__restrict__ grad_attr) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t oi = gid / IBV_LANES;   // output element (ba, v, c)
+    const int slot = (int)(gid - oi * IBV_LANES);
+    const bool live = oi < (int64_t)Ba * Va * C;
+    float s = 0.0f;
+    if (live) {
+        const int c = (int)(oi % C);
+        const int64_t bv = oi / C;
+        const int ba = (int)(bv / Va), v = (int)(bv - (int64_t)ba * Va);
+        const int b0 = (Ba == 1) ? 0 : ba, b1 = (Ba == 1) ? B : ba + 1;
+        for (int j = adj.offsets[v] + slot; j < adj.offsets[v + 1]; j += IBV_LANES) {
+            const int cr = adj.corners[j];
+            const int t = cr / 3, i = cr - 3 * t;
+            float a = 0.0f;
+            for (int b = b0; b < b1; b++) {
+                const int64_t key = (int64_t)b * T + t;
+                for (int e = tt.offsets[key]; e < tt.offsets[key + 1]; e++) {
+                    const int2 ent = tt.entries[e];
+                    a += partial[((int64_t)ent.x * DRESSI_TILE_PIX * K + ent.y) * 3 * C + i * C + c];
+                }
+            }
+            s += a;
         }
     }
-    float *cg = corner_grad + gid * 3 * C;
 #pragma unroll
-    for (int i = 0; i < 3; i++)
-#pragma unroll
-        for (int c = 0; c < IB_CH; c++)
-            if (c0 + c < C) cg[i * C + c0 + c] = acc[i][c];
-}
-
-__global__ void k_interp_vertex_gather(const float *__restrict__ corner_grad, Adjacency adj, int Ba,
-                                       int Va, int T, int C, float *__restrict__ grad_attr) {
-    int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid >= (int64_t)Ba * Va * C) return;
-    int c = (int)(gid % C);
-    int64_t bv = gid / C;
-    int ba = (int)(bv / Va), v = (int)(bv - (int64_t)ba * Va);
-    const float *cgb = corner_grad + (int64_t)ba * T * 3 * C;
-    float s = 0.0f;
-    for (int j = adj.offsets[v]; j < adj.offsets[v + 1]; j++) {
-        int cr = adj.corners[j];
-        s += cgb[(int64_t)cr * C + c];   // corner cr = 3t + i -> [t][i][c]
-    }
-    grad_attr[gid] = s;
+    for (int m = 1; m < IBV_LANES; m <<= 1) s += __shfl_xor(s, m, 64);
+    if (live && slot == 0) grad_attr[oi] = s;
 }
 
 extern "C" int dressi_interpolate_bwd(dressi_ctx *ctx, const float *attr, int Ba, int Va, int C,
@@ -319,6 +343,8 @@ extern "C" int dressi_interpolate_bwd(dressi_ctx *ctx, const float *attr, int Ba
     int64_t n = (int64_t)B * K * H * W;
     if (n > 0 && !grad_out) return dressi_fail(ctx, DRESSI_EINVAL, "interpolate_bwd: null grad_out");
     hipStream_t st = (hipStream_t)stream;
+    if (grad_attr && Va > 0 && ib_stride(C) * K > 160)
+        return dressi_fail(ctx, DRESSI_EINVAL, "interpolate_bwd: ((C + 2) | 1) * K must be at most 160 with grad_attr");
     if (grad_attr && Va > 0) {
         int ntx = tiles_x(W), nt = ntx * tiles_y(H);
         Carver c;
@@ -327,7 +353,6 @@ extern "C" int dressi_interpolate_bwd(dressi_ctx *ctx, const float *attr, int Ba
         size_t o_tmp = c.take(std::max(frag_index ? (size_t)0 : dressi_fragindex_tmp_bytes(B, T),
                                        adj ? (size_t)0 : dressi_adjacency_tmp_bytes(Va)));
         size_t o_part = c.take(sizeof(float) * (size_t)B * nt * DRESSI_TILE_PIX * K * 3 * C);
-        size_t o_cg = c.take(sizeof(float) * 3 * (size_t)C * Ba * T);
         rc = dressi_scratch(ctx, c.off, st);
         if (rc) return rc;
         if (!frag_index) {
@@ -351,21 +376,25 @@ extern "C" int dressi_interpolate_bwd(dressi_ctx *ctx, const float *attr, int Ba
         }
         Adjacency A = adjacency_view(ab, Va);
         float *part = at<float>(S, o_part);
-        float *cg = at<float>(S, o_cg);
-        if ((int64_t)B * nt > 0)
-            DR_LAUNCH("k_interp_bwd_tile", (k_interp_bwd_tile), B * nt, DRESSI_TILE_PIX,
-                      sizeof(float) * (size_t)(C + 2) * DRESSI_TILE_PIX * K, st, attr, Ba, Va, C, attr_tris, T,
-                      tri_id, reinterpret_cast<const float2 *>(bary), K, H, W, ntx, nt, fl, grad_out,
-                      reinterpret_cast<const float2 *>(grad_bary_in), reinterpret_cast<float2 *>(grad_bary),
-                      part);
-        int64_t ntri = (int64_t)Ba * T;
-        if (ntri > 0) {
-            dim3 g((unsigned)((ntri + 255) / 256), (unsigned)((C + IB_CH - 1) / IB_CH));
-            DR_LAUNCH("k_interp_bwd_sum", (k_interp_bwd_sum), g, 256, 0, st, B, Ba, T, K, C, tt, part, cg);
+        if ((int64_t)B * nt > 0) {
+            const size_t lds = sizeof(float) * (size_t)ib_stride(C) * DRESSI_TILE_PIX * K;
+            const bool al8 = (((uintptr_t)attr | (uintptr_t)grad_out) & 7u) == 0;
+            const float2 *b2 = reinterpret_cast<const float2 *>(bary);
+            const float2 *gbi = reinterpret_cast<const float2 *>(grad_bary_in);
+            float2 *gbo = reinterpret_cast<float2 *>(grad_bary);
+            if (al8 && C == 6)
+                DR_LAUNCH("k_interp_bwd_tile", (k_interp_bwd_tile<6>), B * nt, DRESSI_TILE_PIX, lds, st, attr, Ba,
+                          Va, C, attr_tris, T, tri_id, b2, K, H, W, ntx, nt, fl, grad_out, gbi, gbo, part);
+            else if (al8 && C == 2)
+                DR_LAUNCH("k_interp_bwd_tile", (k_interp_bwd_tile<2>), B * nt, DRESSI_TILE_PIX, lds, st, attr, Ba,
+                          Va, C, attr_tris, T, tri_id, b2, K, H, W, ntx, nt, fl, grad_out, gbi, gbo, part);
+            else
+                DR_LAUNCH("k_interp_bwd_tile", (k_interp_bwd_tile<0>), B * nt, DRESSI_TILE_PIX, lds, st, attr, Ba,
+                          Va, C, attr_tris, T, tri_id, b2, K, H, W, ntx, nt, fl, grad_out, gbi, gbo, part);
         }
         int64_t ng = (int64_t)Ba * Va * C;
-        DR_LAUNCH("k_interp_vertex_gather", (k_interp_vertex_gather), (int)((ng + 255) / 256), 256, 0, st,
-                  cg, A, Ba, Va, T, C, grad_attr);
+        DR_LAUNCH("k_interp_bwd_vertex", (k_interp_bwd_vertex), (int)((ng * IBV_LANES + 255) / 256), 256, 0, st,
+                  B, Ba, Va, T, K, C, tt, part, A, grad_attr);
     } else if (grad_bary && n > 0) {
         DR_LAUNCH("k_interp_bwd_bary", (k_interp_bwd_bary), (int)((n + 255) / 256), 256, 0, st,
                   attr, Ba, Va, C, attr_tris, T, tri_id, (int64_t)K * H * W, n, grad_out,

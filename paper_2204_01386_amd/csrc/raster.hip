@@ -12,11 +12,12 @@
 // select, independently of the visiting order, the K smallest distinct keys
 // with the smallest triangle id at each key.
 //
-// Backward: the fragments of every tile are sorted by triangle id in LDS
-// (bitonic sort) into per-tile records; per-record sums of the screen-space
-// vertex gradients are formed in LDS, summed per triangle over the tiles it
-// touches in a fixed order, and gathered per vertex over its corners in
-// ascending order.  No float atomics: results are bitwise reproducible.
+// Backward: the fragments of every tile are sorted by triangle id (wavefront
+// sorts merged by rank in LDS) into per-tile records; per-record sums of the
+// screen-space vertex gradients are formed in LDS; per vertex, each of its
+// corners sums its records over the tiles in a fixed order and the corners
+// are combined in a fixed order.  No float atomics: results are bitwise
+// reproducible.
 #include "dressi_internal.h"
 
 #include <algorithm>
@@ -859,15 +860,55 @@ extern "C" int dressi_rasterize_batched(dressi_ctx *ctx, const float *pos_clip, 
 // ---------------------------------------------------------------------------
 // per-tile fragment lists sorted by triangle id
 // ---------------------------------------------------------------------------
-#define FS_MAXN 2048
-#define FS_SENT 0xffffffffffffffffull   // sort key: triangle id << 11 | local fragment
+// Sort keys are (triangle id << 11 | local fragment k*256 + pixel); an empty
+// slot gets FS_SENT | local, above every fragment key.  All keys of a tile are
+// distinct, so a key's rank is its sorted position.
+#define FS_SENT 0xfffffffffffff800ull
 
+__device__ __forceinline__ unsigned long long shfl_xor_u64(unsigned long long v, int m) {
+    const unsigned lo = __shfl_xor((unsigned)(v & 0xffffffffu), m, 64);
+    const unsigned hi = __shfl_xor((unsigned)(v >> 32), m, 64);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+// bitonic sort of one key per lane across a wavefront, ascending in lane order
+__device__ __forceinline__ unsigned long long wave_sort_u64(unsigned long long v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int k = 2; k <= 64; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            const unsigned long long o = shfl_xor_u64(v, j);
+            const bool up = (lane & k) == 0;   // this lane's block sorts ascending
+            const bool low = (lane & j) == 0;
+            const unsigned long long mn = v < o ? v : o, mx = v < o ? o : v;
+            v = (low == up) ? mn : mx;
+        }
+    }
+    return v;
+}
+
+// number of keys below v in a sorted run of 64
+__device__ __forceinline__ int run_rank(const unsigned long long *run, unsigned long long v) {
+    int lo = 0;
+#pragma unroll
+    for (int s = 32; s >= 1; s >>= 1)
+        if (run[lo + s - 1] < v) lo += s;
+    if (run[lo] < v) lo++;
+    return lo;
+}
+
+// One workgroup per tile: the tile's K*256 keys are sorted in runs of 64 (one
+// wavefront each, in registers), every key is placed at its rank (its index in
+// its run plus its rank in each other run), and the sorted list is cut into
+// per-triangle records.
 __global__ void __launch_bounds__(DRESSI_TILE_PIX)
-    k_fragsort(const int32_t *__restrict__ tri_id, int K, int H, int W, int ntx, int nt, int np, int T,
+    k_fragsort(const int32_t *__restrict__ tri_id, int K, int H, int W, int ntx, int nt, int T,
                int32_t *__restrict__ n_frag, int32_t *__restrict__ n_rec, uint16_t *__restrict__ frag,
                int32_t *__restrict__ rec_tri, int32_t *__restrict__ rec_start,
                int32_t *__restrict__ tri_counts) {
-    __shared__ unsigned long long keys[FS_MAXN];
+    __shared__ unsigned long long runs[DRESSI_MAX_K * DRESSI_TILE_PIX];
+    __shared__ unsigned long long keys[DRESSI_MAX_K * DRESSI_TILE_PIX];
     __shared__ int wsum[DRESSI_TILE_PIX / 64];
     const int bt = blockIdx.x;
     const int b = bt / nt, tile = bt - b * nt;
@@ -875,15 +916,17 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX)
     const int p = threadIdx.x;
     const int x = tx * DRESSI_TILE + (p & (DRESSI_TILE - 1));
     const int y = ty * DRESSI_TILE + p / DRESSI_TILE;
-    for (int i = p; i < np; i += DRESSI_TILE_PIX) keys[i] = FS_SENT;
-    __syncthreads();
+    const int np = K * DRESSI_TILE_PIX, nruns = np / 64;
     int any = 0;
-    if (x < W && y < H) {
-        for (int k = 0; k < K; k++) {
-            int t = tri_id[(((int64_t)b * K + k) * H + y) * W + x];
+    unsigned long long kv[DRESSI_MAX_K];
+#pragma unroll
+    for (int k = 0; k < DRESSI_MAX_K; k++) {
+        const int e = k * DRESSI_TILE_PIX + p;
+        kv[k] = FS_SENT | (unsigned long long)e;
+        if (k < K && x < W && y < H) {
+            const int t = tri_id[(((int64_t)b * K + k) * H + y) * W + x];
             if (t >= 0) {
-                keys[k * DRESSI_TILE_PIX + p] =
-                    ((unsigned long long)t << 11) | (unsigned long long)(k * DRESSI_TILE_PIX + p);
+                kv[k] = ((unsigned long long)t << 11) | (unsigned long long)e;
                 any = 1;
             }
         }
@@ -895,29 +938,27 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX)
         }
         return;
     }
-    // bitonic sort of np keys (np a power of two)
-    for (int size = 2; size <= np; size <<= 1) {
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            for (int i = p; i < (np >> 1); i += DRESSI_TILE_PIX) {
-                int lo = 2 * i - (i & (stride - 1));
-                int hi = lo + stride;
-                bool asc = (lo & size) == 0;
-                unsigned long long a = keys[lo], c = keys[hi];
-                if ((a > c) == asc) {
-                    keys[lo] = c;
-                    keys[hi] = a;
-                }
-            }
-            __syncthreads();
-        }
+#pragma unroll
+    for (int k = 0; k < DRESSI_MAX_K; k++)
+        if (k < K) runs[k * DRESSI_TILE_PIX + p] = wave_sort_u64(kv[k]);   // run = this wavefront's layer-k keys
+    __syncthreads();
+    for (int k = 0; k < K; k++) {
+        const int e = k * DRESSI_TILE_PIX + p;
+        const int run = e >> 6;
+        const unsigned long long v = runs[e];
+        int pos = e & 63;
+        for (int r2 = 0; r2 < nruns; r2++)
+            if (r2 != run) pos += run_rank(runs + r2 * 64, v);
+        keys[pos] = v;
     }
-    // each thread owns a contiguous run of `per` sorted keys
-    const int per = np / DRESSI_TILE_PIX;
+    __syncthreads();
+    // each thread owns a contiguous run of K sorted keys
+    const int per = K;
     const int i0 = p * per;
     int heads = 0, valid = 0;
     for (int j = 0; j < per; j++) {
         unsigned long long kv = keys[i0 + j];
-        if (kv == FS_SENT) break;
+        if (kv >= FS_SENT) break;
         valid++;
         if (i0 + j == 0 || (keys[i0 + j - 1] >> 11) != (kv >> 11)) heads++;
     }
@@ -944,7 +985,7 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX)
     for (int j = 0; j < per; j++) {
         int i = i0 + j;
         unsigned long long kv = keys[i];
-        if (kv == FS_SENT) break;
+        if (kv >= FS_SENT) break;
         frag[base + i] = (uint16_t)(kv & 2047u);
         if (i == 0 || (keys[i - 1] >> 11) != (kv >> 11)) {
             int t = (int)(kv >> 11);
@@ -957,7 +998,7 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX)
     // number of valid keys = position of the first sentinel (keys are sorted)
     if (valid < per) {
         int i = i0 + valid;
-        if (i == 0 || keys[i - 1] != FS_SENT) n_frag[bt] = i;
+        if (i == 0 || keys[i - 1] < FS_SENT) n_frag[bt] = i;
     } else if (p == DRESSI_TILE_PIX - 1) {
         n_frag[bt] = np;
     }
@@ -1040,10 +1081,8 @@ void dressi_build_fragindex(const int32_t *tri_id, int B, int K, int H, int W, i
     TriTiles tt;
     dressi_fragindex_view(base, B, K, H, W, T, fl, tt);
     int ntx = tiles_x(W), nt = ntx * tiles_y(H);
-    int np = 256;
-    while (np < DRESSI_TILE_PIX * K) np <<= 1;
     if (B * nt > 0)
-        DR_LAUNCH("k_fragsort", (k_fragsort), B * nt, DRESSI_TILE_PIX, 0, s, tri_id, K, H, W, ntx, nt, np, T,
+        DR_LAUNCH("k_fragsort", (k_fragsort), B * nt, DRESSI_TILE_PIX, 0, s, tri_id, K, H, W, ntx, nt, T,
                   fl.n_frag, fl.n_rec, fl.frag, fl.rec_tri, fl.rec_start, counts);
     int64_t n = (int64_t)B * T;
     dressi_exclusive_scan(counts, tt.offsets, n, tmp, s);
@@ -1098,9 +1137,8 @@ __device__ __forceinline__ void frag_range(const FragLists &fl, int64_t bt, int6
 //    direct w term) of its triangle's three corners, kept in LDS; the tile's
 //    fragments are already sorted by triangle, so each triangle's fragments are
 //    summed in that order into one record (a segmented sum);
-// 2. per (view, triangle): its records summed in tile order, then mapped from
-//    screen to clip space;
-// 3. per (view, vertex): its corners summed in ascending order.
+// 2. per (view, vertex): each corner's records summed in tile order and mapped
+//    from screen to clip space, the corners combined in a fixed order.
 // ---------------------------------------------------------------------------
 
 // gradient of one fragment: out[corner*3 + {0,1,2}] = d/dx_screen, d/dy_screen,
@@ -1247,60 +1285,51 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX)
     }
 }
 
-// per (view, triangle): sum its tile records, map screen -> clip
-// (x_s = (x/w + 1) W/2, y_s = (1 - y/w) H/2)
-__global__ void k_rast_bwd_sum(const float4 *__restrict__ pos_clip, const int32_t *__restrict__ tris,
-                               Viewports vp, int B, int V, int T, int H, int W, int K, TriTiles tt,
-                               const float *__restrict__ partial, float *__restrict__ corner_grad) {
-    int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid >= (int64_t)B * T) return;
-    int b = (int)(gid / T), t = (int)(gid - (int64_t)b * T);
-    double acc[9];
-#pragma unroll
-    for (int c = 0; c < 9; c++) acc[c] = 0.0;
-    for (int e = tt.offsets[gid]; e < tt.offsets[gid + 1]; e++) {
-        int2 ent = tt.entries[e];
-        const float *v = partial + ((int64_t)ent.x * DRESSI_TILE_PIX * K + ent.y) * 9;
-#pragma unroll
-        for (int c = 0; c < 9; c++) acc[c] += (double)v[c];
-    }
-    float *cg = corner_grad + gid * 9;
-    const int32_t *tv = tris + 3 * (int64_t)t;
-    const int4 q = dr_viewport(vp, t, H, W);
-    const double hw = 0.5 * (double)q.z, hh = 0.5 * (double)q.w;
-#pragma unroll
-    for (int i = 0; i < 3; i++) {
-        int v = tv[i];
-        if (v < 0 || v >= V) {
-            cg[3 * i] = cg[3 * i + 1] = cg[3 * i + 2] = 0.0f;
-            continue;
-        }
-        float4 p = pos_clip[(int64_t)b * V + v];
-        double w = p.w, xn = (double)(p.x / p.w), yn = (double)(p.y / p.w);
-        double gsx = acc[3 * i], gsy = acc[3 * i + 1];
-        cg[3 * i + 0] = (float)(gsx * hw / w);
-        cg[3 * i + 1] = (float)(-gsy * hh / w);
-        cg[3 * i + 2] = (float)((-gsx * hw * xn + gsy * hh * yn) / w + acc[3 * i + 2]);
-    }
-}
-
-// one thread per (view, vertex): sum the corner gradients of its triangles in
-// ascending corner order
-__global__ void k_vertex_gather_pos(const float *__restrict__ corner_grad, Adjacency adj, int B,
-                                    int V, int T, float4 *__restrict__ grad_pos) {
-    int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid >= (int64_t)B * V) return;
-    int b = (int)(gid / V), v = (int)(gid - (int64_t)b * V);
+// Eight lanes per (view, vertex); lane j takes the vertex's corners j, j+8,
+// ... in ascending order.  Each corner's tile records are summed in tile
+// order (double) and mapped from screen to clip space at the vertex
+// (x_s = (x/w + 1) W/2, y_s = (1 - y/w) H/2, with the triangle's view size),
+// rounded to float and added to the lane's sum; the eight lane sums are then
+// combined in a fixed butterfly order.
+#define RBV_LANES 8
+__global__ void k_rast_bwd_vertex(const float4 *__restrict__ pos_clip, Viewports vp, int B, int V, int T, int H,
+                                  int W, int K, TriTiles tt, const float *__restrict__ partial, Adjacency adj,
+                                  float4 *__restrict__ grad_pos) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t vid = gid / RBV_LANES;
+    const int slot = (int)(gid - vid * RBV_LANES);
+    const bool live = vid < (int64_t)B * V;
     float gx = 0.0f, gy = 0.0f, gw = 0.0f;
-    const float *cgb = corner_grad + (int64_t)b * T * 9;
-    for (int j = adj.offsets[v]; j < adj.offsets[v + 1]; j++) {
-        int c = adj.corners[j];
-        const float *g = cgb + (int64_t)(c / 3) * 9 + (c % 3) * 3;
-        gx += g[0];
-        gy += g[1];
-        gw += g[2];
+    if (live) {
+        const int b = (int)(vid / V), v = (int)(vid - (int64_t)b * V);
+        const float4 p = pos_clip[vid];
+        const double iw = 1.0 / (double)p.w, xn = (double)(p.x / p.w), yn = (double)(p.y / p.w);
+        for (int j = adj.offsets[v] + slot; j < adj.offsets[v + 1]; j += RBV_LANES) {
+            const int c = adj.corners[j];
+            const int t = c / 3, i = c - 3 * t;
+            const int64_t key = (int64_t)b * T + t;
+            double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+            for (int e = tt.offsets[key]; e < tt.offsets[key + 1]; e++) {
+                const int2 ent = tt.entries[e];
+                const float *r = partial + ((int64_t)ent.x * DRESSI_TILE_PIX * K + ent.y) * 9 + 3 * i;
+                a0 += (double)r[0];
+                a1 += (double)r[1];
+                a2 += (double)r[2];
+            }
+            const int4 q = dr_viewport(vp, t, H, W);
+            const double hw = 0.5 * (double)q.z, hh = 0.5 * (double)q.w;
+            gx += (float)(a0 * hw * iw);
+            gy += (float)(-a1 * hh * iw);
+            gw += (float)((-a0 * hw * xn + a1 * hh * yn) * iw + a2);
+        }
     }
-    grad_pos[gid] = make_float4(gx, gy, 0.0f, gw);
+#pragma unroll
+    for (int m = 1; m < RBV_LANES; m <<= 1) {
+        gx += __shfl_xor(gx, m, 64);
+        gy += __shfl_xor(gy, m, 64);
+        gw += __shfl_xor(gw, m, 64);
+    }
+    if (live && slot == 0) grad_pos[vid] = make_float4(gx, gy, 0.0f, gw);
 }
 
 static size_t partial_floats(int B, int K, int H, int W, int per) {
@@ -1326,7 +1355,6 @@ static int rasterize_bwd_impl(dressi_ctx *ctx, const float *pos_clip, const int3
     size_t o_tmp = c.take(std::max(frag_index ? (size_t)0 : dressi_fragindex_tmp_bytes(B, T),
                                    adj ? (size_t)0 : dressi_adjacency_tmp_bytes(V)));
     size_t o_part = c.take(sizeof(float) * partial_floats(B, K, H, W, 9));
-    size_t o_cg = c.take(sizeof(float) * 9 * (size_t)B * T);
     rc = dressi_scratch(ctx, c.off, st);
     if (rc) return rc;
     if (!frag_index) {
@@ -1350,19 +1378,15 @@ static int rasterize_bwd_impl(dressi_ctx *ctx, const float *pos_clip, const int3
     }
     Adjacency A = adjacency_view(ab, V);
     float *part = at<float>(S, o_part);
-    float *cg = at<float>(S, o_cg);
-    int64_t ntri = (int64_t)B * T;
     if ((int64_t)B * nt > 0)
         DR_LAUNCH("k_rast_bwd_tile", (k_rast_bwd_tile), B * nt, DRESSI_TILE_PIX,
                   sizeof(float) * 9 * DRESSI_TILE_PIX * K, st, reinterpret_cast<const float4 *>(pos_clip), tris,
                   vp, V, T, H, W, K, cull, margin, tri_id, fl, ntx, nt,
                   reinterpret_cast<const float2 *>(grad_bary), grad_dist, part);
-    if (ntri > 0)
-        DR_LAUNCH("k_rast_bwd_sum", (k_rast_bwd_sum), (int)((ntri + 255) / 256), 256, 0, st,
-                  reinterpret_cast<const float4 *>(pos_clip), tris, vp, B, V, T, H, W, K, tt, part, cg);
     int64_t nv = (int64_t)B * V;
-    DR_LAUNCH("k_vertex_gather_pos", (k_vertex_gather_pos), (int)((nv + 255) / 256), 256, 0, st, cg, A, B,
-              V, T, reinterpret_cast<float4 *>(grad_pos_clip));
+    DR_LAUNCH("k_rast_bwd_vertex", (k_rast_bwd_vertex), (int)((nv * RBV_LANES + 255) / 256), 256, 0, st,
+              reinterpret_cast<const float4 *>(pos_clip), vp, B, V, T, H, W, K, tt, part, A,
+              reinterpret_cast<float4 *>(grad_pos_clip));
     return dressi_launch_check(ctx, "rasterize_bwd");
 }
 

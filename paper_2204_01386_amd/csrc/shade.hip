@@ -498,6 +498,76 @@ __global__ void __launch_bounds__(LOSS_BS)
     if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
+// The same with four pixels per thread and 16-byte accesses (every base
+// 16-byte aligned, per_block a multiple of 4 * LOSS_BS); a block's last
+// pixels that do not fill a quad are taken by its first thread.  Each pixel's
+// terms are formed exactly as above.
+__device__ __forceinline__ float loss_px(float c0, float c1, float c2, float s, float4 t, float w, bool wt,
+                                         float &g0, float &g1, float &g2, float &g3, float &acc) {
+    float d0 = c0 - t.x, d1 = c1 - t.y, d2 = c2 - t.z;
+    float d3 = s - t.w;
+    const float sq = d0 * d0 + d1 * d1 + d2 * d2 + d3 * d3;
+    acc += wt ? w * sq : sq;
+    g0 = 2.0f * w * d0;
+    g1 = 2.0f * w * d1;
+    g2 = 2.0f * w * d2;
+    g3 = 2.0f * w * d3;
+    return sq;
+}
+
+__global__ void __launch_bounds__(LOSS_BS)
+    k_loss_l2_v4(const float *__restrict__ color, const float *__restrict__ sil,
+                 const float *__restrict__ target, const float *__restrict__ weight, int64_t n,
+                 int64_t per_block, float inv, float *__restrict__ grad_color, float *__restrict__ grad_sil,
+                 float *__restrict__ partial) {
+    __shared__ float red[LOSS_BS];
+    float acc = 0.0f;
+    const bool wt = weight != nullptr;
+    const int64_t i0 = (int64_t)blockIdx.x * per_block, i1 = min(n, i0 + per_block);
+    const int64_t q1 = i0 + (i1 - i0) / 4 * 4;
+    for (int64_t i = i0 + 4 * (int64_t)threadIdx.x; i < q1; i += 4 * LOSS_BS) {
+        const float4 *c4 = reinterpret_cast<const float4 *>(color + 3 * i);
+        const float4 ca = c4[0], cb = c4[1], cc = c4[2];
+        const float4 s4 = *reinterpret_cast<const float4 *>(sil + i);
+        const float4 *t4 = reinterpret_cast<const float4 *>(target) + i;
+        const float4 ta = t4[0], tb = t4[1], tc = t4[2], td = t4[3];
+        const float4 w4 = wt ? *reinterpret_cast<const float4 *>(weight + i) : make_float4(inv, inv, inv, inv);
+        float g[12], gs[4];
+        loss_px(ca.x, ca.y, ca.z, s4.x, ta, w4.x, wt, g[0], g[1], g[2], gs[0], acc);
+        loss_px(ca.w, cb.x, cb.y, s4.y, tb, w4.y, wt, g[3], g[4], g[5], gs[1], acc);
+        loss_px(cb.z, cb.w, cc.x, s4.z, tc, w4.z, wt, g[6], g[7], g[8], gs[2], acc);
+        loss_px(cc.y, cc.z, cc.w, s4.w, td, w4.w, wt, g[9], g[10], g[11], gs[3], acc);
+        if (grad_color) {
+            float4 *o = reinterpret_cast<float4 *>(grad_color + 3 * i);
+            o[0] = make_float4(g[0], g[1], g[2], g[3]);
+            o[1] = make_float4(g[4], g[5], g[6], g[7]);
+            o[2] = make_float4(g[8], g[9], g[10], g[11]);
+        }
+        if (grad_sil) *reinterpret_cast<float4 *>(grad_sil + i) = make_float4(gs[0], gs[1], gs[2], gs[3]);
+    }
+    if (threadIdx.x == 0) {
+        for (int64_t i = q1; i < i1; i++) {
+            const float w = wt ? weight[i] : inv;
+            float g0, g1, g2, g3;
+            loss_px(color[3 * i], color[3 * i + 1], color[3 * i + 2], sil[i],
+                    reinterpret_cast<const float4 *>(target)[i], w, wt, g0, g1, g2, g3, acc);
+            if (grad_color) {
+                grad_color[3 * i] = g0;
+                grad_color[3 * i + 1] = g1;
+                grad_color[3 * i + 2] = g2;
+            }
+            if (grad_sil) grad_sil[i] = g3;
+        }
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = LOSS_BS / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
 __global__ void __launch_bounds__(LOSS_BS)
     k_loss_sum(const float *__restrict__ partial, int nb, float scale, float *__restrict__ loss) {
     __shared__ float red[LOSS_BS];
@@ -527,7 +597,7 @@ extern "C" int dressi_loss_l2(dressi_ctx *ctx, const float *color, const float *
     if (nb > LOSS_MAX_BLOCKS) {
         nb = LOSS_MAX_BLOCKS;
         per = (n + nb - 1) / nb;
-        per = (per + LOSS_BS - 1) / LOSS_BS * LOSS_BS;
+        per = (per + 4 * LOSS_BS - 1) / (4 * LOSS_BS) * (4 * LOSS_BS);
         nb = (n + per - 1) / per;
     }
     if (nb < 1) nb = 1;
@@ -537,8 +607,14 @@ extern "C" int dressi_loss_l2(dressi_ctx *ctx, const float *color, const float *
     if (rc) return rc;
     float *partial = at<float>(ctx->scratch, o_p);
     float inv = 1.0f / (4.0f * (float)(n > 0 ? n : 1));
-    DR_LAUNCH("k_loss_l2", (k_loss_l2), (int)nb, LOSS_BS, 0, st, color, sil, target, weight, n, per, inv,
-              grad_color, grad_sil, partial);
+    const uintptr_t al = (uintptr_t)color | (uintptr_t)sil | (uintptr_t)target | (uintptr_t)weight |
+                         (uintptr_t)grad_color | (uintptr_t)grad_sil;
+    if ((al & 15u) == 0)
+        DR_LAUNCH("k_loss_l2", (k_loss_l2_v4), (int)nb, LOSS_BS, 0, st, color, sil, target, weight, n, per, inv,
+                  grad_color, grad_sil, partial);
+    else
+        DR_LAUNCH("k_loss_l2", (k_loss_l2), (int)nb, LOSS_BS, 0, st, color, sil, target, weight, n, per, inv,
+                  grad_color, grad_sil, partial);
     DR_LAUNCH("k_loss_sum", (k_loss_sum), 1, LOSS_BS, 0, st, partial, (int)nb, weight ? 1.0f : inv, loss);
     return dressi_launch_check(ctx, "loss_l2");
 }

@@ -271,17 +271,20 @@ __global__ void __launch_bounds__(256)
 // weight on this texel times its gradient.  A 16x16 block of texels loads the
 // 18x18 halo of cells of DRESSI_IV_SG slices at once (all loads in flight), skips the
 // group when every cell is empty, then gathers.  With nsplit > 1 the slice
-// range is split over grid.z and each part writes its own partial sum.
-template <int CT>
+// range is split over grid.z and each part writes its own partial sum.  SG
+// slices are staged at a time (SG = 1 for a single slice keeps the LDS small
+// and the occupancy high).  A winner found in a cell of face or layer f has
+// its taps on f, so they are recomputed from its coordinate alone.
+template <int CT, int SG>
 __global__ void __launch_bounds__(IV_T * IV_T)
     k_invuv_gather(dressi_tex_desc td, const float *__restrict__ coord, const int32_t *__restrict__ tri_id,
                    int64_t npix, int S, int nsplit, const int32_t *__restrict__ inv,
                    const float *__restrict__ grad_out, float *__restrict__ out) {
     // per halo cell of each slice of the group: the winner pixel (-1: none or
     // another cube face), its four tap coordinates and bilinear fractions
-    __shared__ int cpix[DRESSI_IV_SG][IV_H * IV_H];
-    __shared__ int2 ctap[DRESSI_IV_SG][IV_H * IV_H];   // x0 | x1 << 16, y0 | y1 << 16
-    __shared__ float2 cfr[DRESSI_IV_SG][IV_H * IV_H];  // fx, fy
+    __shared__ int cpix[SG][IV_H * IV_H];
+    __shared__ int2 ctap[SG][IV_H * IV_H];   // x0 | x1 << 16, y0 | y1 << 16
+    __shared__ float2 cfr[SG][IV_H * IV_H];  // fx, fy
     const int Ht = td.Ht, Wt = td.Wt, Ct = CT > 0 ? CT : td.Ct;
     const bool cube = td.kind == DRESSI_TEX_CUBE;
     const int F = tex_faces(td);
@@ -316,12 +319,12 @@ __global__ void __launch_bounds__(IV_T * IV_T)
     float acc[TEX_NC(CT)];
 #pragma unroll
     for (int c = 0; c < TEX_NC(CT); c++) acc[c] = 0.0f;
-    for (int g0 = s0; g0 < s1; g0 += DRESSI_IV_SG) {
-        const int ng = min(DRESSI_IV_SG, s1 - g0);
+    for (int g0 = s0; g0 < s1; g0 += SG) {
+        const int ng = min(SG, s1 - g0);
         // winners of the group's halo cells (all loads in flight)
-        int wpix[DRESSI_IV_SG][2];
+        int wpix[SG][2];
 #pragma unroll
-        for (int q = 0; q < DRESSI_IV_SG; q++) {
+        for (int q = 0; q < SG; q++) {
             const int32_t *iv = inv + (int64_t)(g0 + q) * cells_all + (int64_t)f * face_cells;
 #pragma unroll
             for (int k = 0; k < 2; k++) wpix[q][k] = (q < ng && hoff[k] >= 0) ? iv[hoff[k]] : -1;
@@ -329,7 +332,7 @@ __global__ void __launch_bounds__(IV_T * IV_T)
         int found = 0;
         // each winner's taps, computed once for the up to 9 texels that visit it
 #pragma unroll
-        for (int q = 0; q < DRESSI_IV_SG; q++) {
+        for (int q = 0; q < SG; q++) {
 #pragma unroll
             for (int k = 0; k < 2; k++) {
                 const int h = threadIdx.x + k * IV_T * IV_T;
@@ -339,7 +342,7 @@ __global__ void __launch_bounds__(IV_T * IV_T)
                 float2 fr = make_float2(0.0f, 0.0f);
                 if (i >= 0) {
                     const int64_t o = (int64_t)(g0 + q) * npix + i;
-                    const Taps t = make_taps(td, coord + o * cd, tex_layer(td, tri_id, o));
+                    const Taps t = make_taps(td, coord + o * cd, f);
                     if (!t.ok || t.face != f) {
                         i = -1;
                     } else {
@@ -396,6 +399,24 @@ __global__ void k_invuv_reduce(const float *__restrict__ part, int nsplit, int64
     float a = part[i];
     for (int k = 1; k < nsplit; k++) a += part[(int64_t)k * n + i];
     out[i] = a;
+}
+
+template <int SG>
+static void launch_gather(int ct, dim3 g, hipStream_t st, const dressi_tex_desc &td, const float *coord,
+                          const int32_t *tri_id, int64_t npix, int S, int nsplit, const int32_t *inv,
+                          const float *grad_out, float *dst) {
+    if (ct == 4)
+        DR_LAUNCH("k_invuv_gather", (k_invuv_gather<4, SG>), g, IV_T * IV_T, 0, st, td, coord, tri_id, npix, S,
+                  nsplit, inv, grad_out, dst);
+    else if (ct == 3)
+        DR_LAUNCH("k_invuv_gather", (k_invuv_gather<3, SG>), g, IV_T * IV_T, 0, st, td, coord, tri_id, npix, S,
+                  nsplit, inv, grad_out, dst);
+    else if (ct == 8)
+        DR_LAUNCH("k_invuv_gather", (k_invuv_gather<8, SG>), g, IV_T * IV_T, 0, st, td, coord, tri_id, npix, S,
+                  nsplit, inv, grad_out, dst);
+    else
+        DR_LAUNCH("k_invuv_gather", (k_invuv_gather<0, SG>), g, IV_T * IV_T, 0, st, td, coord, tri_id, npix, S,
+                  nsplit, inv, grad_out, dst);
 }
 
 // float4 rows need 16-byte aligned bases
@@ -497,18 +518,8 @@ extern "C" int dressi_texture_bwd(dressi_ctx *ctx, const float *tex, const dress
         dim3 g((unsigned)((td->Wt + IV_T - 1) / IV_T), (unsigned)((td->Ht + IV_T - 1) / IV_T),
                (unsigned)(tex_faces(*td) * nsplit));
         const int ct = aligned16(grad_out, dst) ? td->Ct : 0;
-        if (ct == 4)
-            DR_LAUNCH("k_invuv_gather", (k_invuv_gather<4>), g, IV_T * IV_T, 0, st, *td, coord, tri_id, npix, S, nsplit,
-                      inv, grad_out, dst);
-        else if (ct == 3)
-            DR_LAUNCH("k_invuv_gather", (k_invuv_gather<3>), g, IV_T * IV_T, 0, st, *td, coord, tri_id, npix, S, nsplit,
-                      inv, grad_out, dst);
-        else if (ct == 8)
-            DR_LAUNCH("k_invuv_gather", (k_invuv_gather<8>), g, IV_T * IV_T, 0, st, *td, coord, tri_id, npix, S, nsplit,
-                      inv, grad_out, dst);
-        else
-            DR_LAUNCH("k_invuv_gather", (k_invuv_gather<0>), g, IV_T * IV_T, 0, st, *td, coord, tri_id, npix, S, nsplit,
-                      inv, grad_out, dst);
+        if (S == 1) launch_gather<1>(ct, g, st, *td, coord, tri_id, npix, S, nsplit, inv, grad_out, dst);
+        else launch_gather<DRESSI_IV_SG>(ct, g, st, *td, coord, tri_id, npix, S, nsplit, inv, grad_out, dst);
         if (nsplit > 1) {
             int64_t ne = cells * td->Ct;
             DR_LAUNCH("k_invuv_reduce", (k_invuv_reduce), (int)((ne + 255) / 256), 256, 0, st, part, nsplit, ne,

@@ -562,7 +562,7 @@ def make_batch_target(scenes_list, device="cuda") -> BatchStep:
 # ---------------------------------------------------------------------------
 # autotuning
 # ---------------------------------------------------------------------------
-HARD_RASTER_NAMES = {None: "triangle-parallel", 0: "triangle-parallel", 1: "pixel-parallel", 2: "per-tile"}
+HARD_RASTER_NAMES = {None: "pixel-parallel (soft)", 0: "triangle-parallel", 1: "pixel-parallel", 2: "per-tile"}
 def autotune(step, reps: int = 5) -> dict:
     """Picks the hard-rasterization strategy (triangle-parallel tiles,
     pixel-parallel tiles, or a choice per tile and triangle batch with one of
