@@ -2,9 +2,10 @@
 // shading and the L2 image loss, forward and backward, for gfx950.
 //
 // All of these are memory-bound elementwise or gather kernels.  Per-vertex
-// sums over incident faces go through the vertex->corner adjacency in
-// ascending corner order, and the loss is reduced in a fixed tree order, so
-// every result is bitwise reproducible.
+// sums over incident faces go through the vertex->corner adjacency, each
+// vertex's corners split over a fixed group of lanes combined in a fixed
+// order, and the loss is reduced in a fixed tree order, so every result is
+// bitwise reproducible.
 #include "dressi_internal.h"
 
 // ---------------------------------------------------------------------------
@@ -114,32 +115,70 @@ __device__ __forceinline__ float3 normalize3_bwd(float3 a, float3 g) {
     return (1.0f / l) * (g - dot3(g, n) * n);
 }
 
-__device__ __forceinline__ float3 face_normal(const float *pos, const int32_t *tris, int t, int V,
-                                              int *vid) {
-    int a = tris[3 * t], b = tris[3 * t + 1], c = tris[3 * t + 2];
-    vid[0] = a; vid[1] = b; vid[2] = c;
-    if (a < 0 || a >= V || b < 0 || b >= V || c < 0 || c >= V) return make_float3(0.0f, 0.0f, 0.0f);
-    float3 p0 = ld3(pos + 3 * (int64_t)a);
-    return cross3(ld3(pos + 3 * (int64_t)b) - p0, ld3(pos + 3 * (int64_t)c) - p0);
+// Per-vertex sums over incident faces use VA_LANES lanes per vertex: lane j
+// takes the vertex's corners j, j + VA_LANES, ... in ascending order and the
+// lane sums are combined in a fixed butterfly order (the same in every lane).
+#define VA_LANES 8
+
+__device__ __forceinline__ float3 lanes_sum(float3 s) {
+#pragma unroll
+    for (int m = 1; m < VA_LANES; m <<= 1) {
+        s.x += __shfl_xor(s.x, m, 64);
+        s.y += __shfl_xor(s.y, m, 64);
+        s.z += __shfl_xor(s.z, m, 64);
+    }
+    return s;
 }
 
-// sum of the (area-weighted) normals of the faces around v, corners ascending
-__device__ __forceinline__ float3 vertex_acc(const float *pos, const int32_t *tris, const Adjacency &adj,
-                                            int v, int V) {
-    float3 s = make_float3(0.0f, 0.0f, 0.0f);
-    int vid[3];
-    for (int j = adj.offsets[v]; j < adj.offsets[v + 1]; j++) s = s + face_normal(pos, tris, adj.corners[j] / 3, V, vid);
+struct dbl3 {
+    double x, y, z;
+};
+
+// Face normals, their sums and the normalisation run in double (the vertex
+// normal is rounded to float once, at the end): the shading downstream has
+// max(0, .) kinks whose side should not depend on the summation order.
+__device__ __forceinline__ dbl3 face_normal_d(const float *pos, const int32_t *tris, int t, int V) {
+    const int a = tris[3 * t], b = tris[3 * t + 1], c = tris[3 * t + 2];
+    if (a < 0 || a >= V || b < 0 || b >= V || c < 0 || c >= V) return dbl3{0.0, 0.0, 0.0};
+    const double p0x = pos[3 * (int64_t)a], p0y = pos[3 * (int64_t)a + 1], p0z = pos[3 * (int64_t)a + 2];
+    const double ux = pos[3 * (int64_t)b] - p0x, uy = pos[3 * (int64_t)b + 1] - p0y, uz = pos[3 * (int64_t)b + 2] - p0z;
+    const double vx = pos[3 * (int64_t)c] - p0x, vy = pos[3 * (int64_t)c + 1] - p0y, vz = pos[3 * (int64_t)c + 2] - p0z;
+    return dbl3{uy * vz - uz * vy, uz * vx - ux * vz, ux * vy - uy * vx};
+}
+
+// sum of the (area-weighted) normals of the faces around v (every lane of the
+// vertex gets it; lanes with live = false contribute nothing)
+__device__ __forceinline__ dbl3 vertex_acc(const float *pos, const int32_t *tris, const Adjacency &adj,
+                                          int v, int V, bool live, int slot) {
+    dbl3 s{0.0, 0.0, 0.0};
+    if (live)
+        for (int j = adj.offsets[v] + slot; j < adj.offsets[v + 1]; j += VA_LANES) {
+            const dbl3 f = face_normal_d(pos, tris, adj.corners[j] / 3, V);
+            s.x += f.x;
+            s.y += f.y;
+            s.z += f.z;
+        }
+#pragma unroll
+    for (int m = 1; m < VA_LANES; m <<= 1) {
+        s.x += __shfl_xor(s.x, m, 64);
+        s.y += __shfl_xor(s.y, m, 64);
+        s.z += __shfl_xor(s.z, m, 64);
+    }
     return s;
 }
 
 __global__ void k_vertex_attrs(const float *__restrict__ pos, const int32_t *__restrict__ tris,
                                const float *__restrict__ extra, Adjacency adj, int V, int C,
                                float *__restrict__ out) {
-    int v = blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= V) return;
-    float3 n = normalize3(vertex_acc(pos, tris, adj, v, V));
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int v = (int)(gid / VA_LANES), slot = (int)(gid % VA_LANES);
+    const bool live = v < V;
+    const dbl3 a = vertex_acc(pos, tris, adj, v, V, live, slot);
+    if (!live || slot != 0) return;
+    const double l = sqrt(a.x * a.x + a.y * a.y + a.z * a.z);
+    const double il = l > 0.0 ? 1.0 / l : 0.0;
     float *o = out + (int64_t)v * C;
-    o[0] = n.x; o[1] = n.y; o[2] = n.z;
+    o[0] = (float)(a.x * il); o[1] = (float)(a.y * il); o[2] = (float)(a.z * il);
     o[3] = pos[3 * (int64_t)v]; o[4] = pos[3 * (int64_t)v + 1]; o[5] = pos[3 * (int64_t)v + 2];
     if (C == 9) {
         o[6] = extra[3 * (int64_t)v]; o[7] = extra[3 * (int64_t)v + 1]; o[8] = extra[3 * (int64_t)v + 2];
@@ -150,39 +189,59 @@ __global__ void k_vertex_attrs(const float *__restrict__ pos, const int32_t *__r
 __global__ void k_vertex_attrs_bwd1(const float *__restrict__ pos, const int32_t *__restrict__ tris,
                                     Adjacency adj, int V, int C, const float *__restrict__ g,
                                     float *__restrict__ gacc) {
-    int v = blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= V) return;
-    float3 a = vertex_acc(pos, tris, adj, v, V);
-    float3 r = normalize3_bwd(a, ld3(g + (int64_t)v * C));
-    gacc[3 * (int64_t)v] = r.x;
-    gacc[3 * (int64_t)v + 1] = r.y;
-    gacc[3 * (int64_t)v + 2] = r.z;
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int v = (int)(gid / VA_LANES), slot = (int)(gid % VA_LANES);
+    const bool live = v < V;
+    const dbl3 a = vertex_acc(pos, tris, adj, v, V, live, slot);
+    if (!live || slot != 0) return;
+    // (g - (g.n) n) / |a| with n = a / |a|
+    const double l = sqrt(a.x * a.x + a.y * a.y + a.z * a.z);
+    double rx = 0.0, ry = 0.0, rz = 0.0;
+    if (l > 0.0) {
+        const double il = 1.0 / l;
+        const double nx = a.x * il, ny = a.y * il, nz = a.z * il;
+        const double gx = g[(int64_t)v * C], gy = g[(int64_t)v * C + 1], gz = g[(int64_t)v * C + 2];
+        const double gn = gx * nx + gy * ny + gz * nz;
+        rx = (gx - gn * nx) * il;
+        ry = (gy - gn * ny) * il;
+        rz = (gz - gn * nz) * il;
+    }
+    gacc[3 * (int64_t)v] = (float)rx;
+    gacc[3 * (int64_t)v + 1] = (float)ry;
+    gacc[3 * (int64_t)v + 2] = (float)rz;
 }
 
-// per vertex: position column + grad_pos_in + the corner gradients of the
-// cross products of its faces (n = e1 x e2: ge1 = e2 x gn, ge2 = gn x e1;
-// corner 0 gets -(ge1 + ge2), corner 1 ge1, corner 2 ge2), corners ascending
+// per vertex: the corner gradients of the cross products of its faces
+// (n = e1 x e2: ge1 = e2 x gn, ge2 = gn x e1; corner 0 gets -(ge1 + ge2),
+// corner 1 ge1, corner 2 ge2), lane-split as above, then the position column
+// and grad_pos_in
 __global__ void k_vertex_attrs_bwd2(const float *__restrict__ pos, const int32_t *__restrict__ tris,
                                     Adjacency adj, int V, int C, const float *__restrict__ g,
                                     const float *__restrict__ gin, const float *__restrict__ gacc,
                                     float *__restrict__ grad_pos) {
-    int v = blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= V) return;
-    float3 s = ld3(g + (int64_t)v * C + 3);
-    if (gin) s = s + ld3(gin + 3 * (int64_t)v);
-    for (int j = adj.offsets[v]; j < adj.offsets[v + 1]; j++) {
-        int cr = adj.corners[j];
-        int t = cr / 3, i = cr - 3 * t;
-        int a = tris[3 * t], b = tris[3 * t + 1], c = tris[3 * t + 2];
-        if (a < 0 || a >= V || b < 0 || b >= V || c < 0 || c >= V) continue;
-        float3 gn = ld3(gacc + 3 * (int64_t)a) + ld3(gacc + 3 * (int64_t)b) + ld3(gacc + 3 * (int64_t)c);
-        float3 p0 = ld3(pos + 3 * (int64_t)a);
-        float3 e1 = ld3(pos + 3 * (int64_t)b) - p0, e2 = ld3(pos + 3 * (int64_t)c) - p0;
-        float3 g1 = cross3(e2, gn), g2 = cross3(gn, e1);
-        if (i == 0) s = s - (g1 + g2);
-        else if (i == 1) s = s + g1;
-        else s = s + g2;
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int v = (int)(gid / VA_LANES), slot = (int)(gid % VA_LANES);
+    const bool live = v < V;
+    float3 s = make_float3(0.0f, 0.0f, 0.0f);
+    if (live) {
+        for (int j = adj.offsets[v] + slot; j < adj.offsets[v + 1]; j += VA_LANES) {
+            int cr = adj.corners[j];
+            int t = cr / 3, i = cr - 3 * t;
+            int a = tris[3 * t], b = tris[3 * t + 1], c = tris[3 * t + 2];
+            if (a < 0 || a >= V || b < 0 || b >= V || c < 0 || c >= V) continue;
+            float3 gn = ld3(gacc + 3 * (int64_t)a) + ld3(gacc + 3 * (int64_t)b) + ld3(gacc + 3 * (int64_t)c);
+            float3 p0 = ld3(pos + 3 * (int64_t)a);
+            float3 e1 = ld3(pos + 3 * (int64_t)b) - p0, e2 = ld3(pos + 3 * (int64_t)c) - p0;
+            float3 g1 = cross3(e2, gn), g2 = cross3(gn, e1);
+            if (i == 0) s = s - (g1 + g2);
+            else if (i == 1) s = s + g1;
+            else s = s + g2;
+        }
     }
+    s = lanes_sum(s);
+    if (!live || slot != 0) return;
+    s = s + ld3(g + (int64_t)v * C + 3);
+    if (gin) s = s + ld3(gin + 3 * (int64_t)v);
     grad_pos[3 * (int64_t)v] = s.x;
     grad_pos[3 * (int64_t)v + 1] = s.y;
     grad_pos[3 * (int64_t)v + 2] = s.z;
@@ -208,7 +267,8 @@ extern "C" int dressi_vertex_attrs(dressi_ctx *ctx, const float *pos, const int3
     }
     Adjacency A = adjacency_view(ab, V);
     int C = extra ? 9 : 6;
-    DR_LAUNCH("k_vertex_attrs", (k_vertex_attrs), (V + 255) / 256, 256, 0, st, pos, tris, extra, A, V, C, out);
+    const int nb = (int)(((int64_t)V * VA_LANES + 255) / 256);
+    DR_LAUNCH("k_vertex_attrs", (k_vertex_attrs), nb, 256, 0, st, pos, tris, extra, A, V, C, out);
     return dressi_launch_check(ctx, "vertex_attrs");
 }
 
@@ -237,10 +297,10 @@ extern "C" int dressi_vertex_attrs_bwd(dressi_ctx *ctx, const float *pos, const 
     }
     Adjacency A = adjacency_view(ab, V);
     float *ga = at<float>(S, o_ga);
-    DR_LAUNCH("k_vertex_attrs_bwd1", (k_vertex_attrs_bwd1), (V + 255) / 256, 256, 0, st, pos, tris, A, V, C,
-              grad_out, ga);
-    DR_LAUNCH("k_vertex_attrs_bwd2", (k_vertex_attrs_bwd2), (V + 255) / 256, 256, 0, st, pos, tris, A, V, C,
-              grad_out, grad_pos_in, ga, grad_pos);
+    const int nb = (int)(((int64_t)V * VA_LANES + 255) / 256);
+    DR_LAUNCH("k_vertex_attrs_bwd1", (k_vertex_attrs_bwd1), nb, 256, 0, st, pos, tris, A, V, C, grad_out, ga);
+    DR_LAUNCH("k_vertex_attrs_bwd2", (k_vertex_attrs_bwd2), nb, 256, 0, st, pos, tris, A, V, C, grad_out,
+              grad_pos_in, ga, grad_pos);
     return dressi_launch_check(ctx, "vertex_attrs_bwd");
 }
 

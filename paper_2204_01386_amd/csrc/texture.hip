@@ -285,6 +285,9 @@ __global__ void __launch_bounds__(IV_T * IV_T)
     __shared__ int cpix[SG][IV_H * IV_H];
     __shared__ int2 ctap[SG][IV_H * IV_H];   // x0 | x1 << 16, y0 | y1 << 16
     __shared__ float2 cfr[SG][IV_H * IV_H];  // fx, fy
+    // one slice at a time: the winners' pixel gradients are staged as well
+    constexpr bool STAGE_G = SG == 1;
+    __shared__ float cg[STAGE_G ? IV_H * IV_H * TEX_NC(CT) : 1];
     const int Ht = td.Ht, Wt = td.Wt, Ct = CT > 0 ? CT : td.Ct;
     const bool cube = td.kind == DRESSI_TEX_CUBE;
     const int F = tex_faces(td);
@@ -348,6 +351,13 @@ __global__ void __launch_bounds__(IV_T * IV_T)
                     } else {
                         tp = make_int2(t.x0 | (t.x1 << 16), t.y0 | (t.y1 << 16));
                         fr = make_float2(t.fx, t.fy);
+                        if constexpr (STAGE_G) {
+                            float g[TEX_NC(CT)];
+                            ldv<CT>(grad_out + o * Ct, g, Ct);
+#pragma unroll
+                            for (int c = 0; c < TEX_NC(CT); c++)
+                                if (CT > 0 || c < Ct) cg[h * TEX_NC(CT) + c] = g[c];
+                        }
                     }
                 }
                 cpix[q][h] = i;
@@ -377,7 +387,13 @@ __global__ void __launch_bounds__(IV_T * IV_T)
                         if (y1 == ty && x1 == tx) w += fr.y * fr.x;
                         if (w == 0.0f) continue;
                         float g[TEX_NC(CT)];
-                        ldv<CT>(grad_out + ((int64_t)s * npix + i) * Ct, g, Ct);
+                        if constexpr (STAGE_G) {
+#pragma unroll
+                            for (int c = 0; c < TEX_NC(CT); c++)
+                                if (CT > 0 || c < Ct) g[c] = cg[h * TEX_NC(CT) + c];
+                        } else {
+                            ldv<CT>(grad_out + ((int64_t)s * npix + i) * Ct, g, Ct);
+                        }
 #pragma unroll
                         for (int c = 0; c < TEX_NC(CT); c++)
                             if (CT > 0 || c < Ct) acc[c] += w * g[c];
