@@ -224,7 +224,7 @@ def measure(scene, steps, warmup, prof_steps, plain_steps_min=10):
     import torch
 
     from paper_2204_01386_amd import binding as Bd
-    from paper_2204_01386_amd.pipeline import Step, autotune, make_target
+    from paper_2204_01386_amd.pipeline import Step, autotune, autotune_streams, make_target
 
     B = scene.mvp.shape[0]
     tgt = make_target(scene)
@@ -238,6 +238,7 @@ def measure(scene, steps, warmup, prof_steps, plain_steps_min=10):
     if ctx.check_status() != 0:
         raise SystemExit("tile-bin capacity overflow during warm-up")
     tuned = autotune(st)
+    tuned["streams"] = autotune_streams(st)
     st.run()
     torch.cuda.synchronize()
     graph = torch.cuda.CUDAGraph()
@@ -270,7 +271,8 @@ def measure(scene, steps, warmup, prof_steps, plain_steps_min=10):
     if prof_steps < 0:
         return res
 
-    # ---- plain: eager calls, one view per call -----------------------------
+    # ---- plain: eager calls on one stream, one view per call ---------------
+    conc, st.concurrent = st.concurrent, False
     if B == 1:
         plain_steps = [st]
     else:
@@ -292,12 +294,13 @@ def measure(scene, steps, warmup, prof_steps, plain_steps_min=10):
     res["plain_ms_per_step"] = e0.elapsed_time(e1) / n_plain
     del plain_steps
 
-    # ---- per-kernel timing ------------------------------------------------
+    # ---- per-kernel timing (one stream: every kernel timed alone) ---------
     cap = 400 * max(prof_steps, 1)
     Bd._lib.dressi_profile_start(cap)
     for _ in range(prof_steps):
         st.run()
     torch.cuda.synchronize()
+    st.concurrent = conc
     names = (C.c_char_p * cap)()
     ms = (C.c_float * cap)()
     n = Bd._lib.dressi_profile_read(names, ms, cap)
@@ -332,10 +335,12 @@ def measure_batch(scene_list, steps, warmup, prof_steps):
     import torch
 
     from paper_2204_01386_amd import binding as Bd
-    from paper_2204_01386_amd.pipeline import BatchStep, Step, autotune, make_batch_target, make_target
+    from paper_2204_01386_amd.pipeline import (BatchStep, Step, autotune, autotune_streams, make_batch_target,
+                                               make_target)
 
     bs = BatchStep(scene_list, target=make_batch_target(scene_list))
     tuned = autotune(bs)
+    tuned["streams"] = autotune_streams(bs, reps=5)
     ctx = Bd.context()
     for _ in range(3):
         bs.run()
@@ -380,7 +385,8 @@ def measure_batch(scene_list, steps, warmup, prof_steps):
     for ps in plain:
         step_bytes += sum(call_bytes(Shapes(ps, int((ps.tri_id >= 0).sum().item()))).values())
     del plain
-    # per-kernel times of the batched step
+    # per-kernel times of the batched step (one stream: every kernel timed alone)
+    bs.concurrent = False
     cap = 400 * max(prof_steps, 1)
     Bd._lib.dressi_profile_start(cap)
     for _ in range(prof_steps):
@@ -415,14 +421,21 @@ def uneven_line(steps, prof_steps):
             "batched_vs_plain_speedup": round(m["plain_ms_per_step"] / m["ms_per_step"], 3),
             "step_alg_bytes": m["step_alg_bytes"],
             "step_hbm_frac": round(m["step_alg_bytes"] / (m["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-            "autotune": {"hard_raster": _strategy_name(m["tuned"]["hard_raster"], m["tuned"]["hybrid_weight"]),
-                         "raster_ms": {_strategy_name(*k): round(v, 4) for k, v in m["tuned"]["ms"].items()}},
+            "autotune": _tuned_json(m["tuned"]),
             "kernels": [{"kernel": k, "ms_per_step": round(v, 5)} for k, v in m["table"][:12]]}
 
 
 def _strategy_name(hr, w):
     from paper_2204_01386_amd.pipeline import HARD_RASTER_NAMES
     return HARD_RASTER_NAMES[hr] + (f" (weight {w}/16)" if hr == 2 else "")
+
+
+def _tuned_json(t):
+    name = {False: "one stream", True: "two streams"}
+    return {"hard_raster": _strategy_name(t["hard_raster"], t["hybrid_weight"]),
+            "raster_ms": {_strategy_name(*k): round(v, 4) for k, v in t["ms"].items()},
+            "schedule": name[t["streams"]["concurrent"]],
+            "step_ms": {name[k]: round(v, 4) for k, v in t["streams"]["ms"].items()}}
 
 
 def main():
@@ -459,8 +472,7 @@ def main():
                     "launches_per_step": c, "alg_bytes": kernel_bytes(k, z)} for k, a, b, c in table]
     ms_plain = m["plain_ms_per_step"]
     launch_rows = [{"launch": k, "ms": round(a, 5)} for k, a in m["launches"][:16]]
-    tuned = {"hard_raster": _strategy_name(m["tuned"]["hard_raster"], m["tuned"]["hybrid_weight"]),
-             "raster_ms": {_strategy_name(*k): round(v, 4) for k, v in m["tuned"]["ms"].items()}}
+    tuned = _tuned_json(m["tuned"])
     del m
 
     # ---- the 16-view batched configuration beside its per-view form -------

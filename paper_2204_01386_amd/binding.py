@@ -153,6 +153,19 @@ def context(device=None) -> Context:
         return _ctxs[d]
 
 
+_aux_ctxs: dict[int, Context] = {}
+
+
+def context_aux(device=None) -> Context:
+    """A second context per device (its own scratch arena) for work issued on
+    a second stream while the first context's calls run on the main stream."""
+    d = torch.cuda.current_device() if device is None else int(device)
+    with _ctx_lock:
+        if d not in _aux_ctxs:
+            _aux_ctxs[d] = Context(d)
+        return _aux_ctxs[d]
+
+
 def _stream(stream=None):
     s = torch.cuda.current_stream() if stream is None else stream
     return C.c_void_p(s.cuda_stream)

@@ -258,36 +258,44 @@ __global__ void __launch_bounds__(256)
     gc[2] = g3[2];
 }
 
-// Texture gradient through the inverse UV.  One 16x16 block of texels per
-// workgroup: per slice the 18x18 cells around the block are staged in LDS
+// Texture gradient through the inverse UV.  One block of texels (16 columns,
+// 32 rows for a single slice, else 16) per workgroup: per slice the cells
+// around the block (a one-cell halo) are staged in LDS
 // (wrapped, or -1 outside a clamped texture); blocks whose cells are all
 // empty skip the slice.  Each texel then visits its 3x3 cells in row-major
 // order and adds the kept pixel's gradient times that pixel's bilinear
 // weight on the texel.
 #define IV_T 16
-#define IV_H (IV_T + 2)
 // Per texel: the sum over slices [s0, s1), in ascending order, of the distinct
 // in-range cells of its 3x3 block, row-major, of the winner pixel's bilinear
-// weight on this texel times its gradient.  A 16x16 block of texels loads the
-// 18x18 halo of cells of DRESSI_IV_SG slices at once (all loads in flight), skips the
+// weight on this texel times its gradient.  A block of texels loads the
+// haloed cells of DRESSI_IV_SG slices at once (all loads in flight), skips the
 // group when every cell is empty, then gathers.  With nsplit > 1 the slice
 // range is split over grid.z and each part writes its own partial sum.  SG
 // slices are staged at a time (SG = 1 for a single slice keeps the LDS small
 // and the occupancy high).  A winner found in a cell of face or layer f has
 // its taps on f, so they are recomputed from its coordinate alone.
+template <int SG>
+struct IvGeom {
+    static constexpr int TY = SG == 1 ? 32 : 16;   // texel rows per block (16 columns)
+    static constexpr int NT = IV_T * TY;           // threads
+    static constexpr int HW = IV_T + 2, HH = TY + 2, HN = HW * HH;   // halo
+};
+
 template <int CT, int SG>
-__global__ void __launch_bounds__(IV_T * IV_T)
+__global__ void __launch_bounds__(IvGeom<SG>::NT)
     k_invuv_gather(dressi_tex_desc td, const float *__restrict__ coord, const int32_t *__restrict__ tri_id,
                    int64_t npix, int S, int nsplit, const int32_t *__restrict__ inv,
                    const float *__restrict__ grad_out, float *__restrict__ out) {
     // per halo cell of each slice of the group: the winner pixel (-1: none or
     // another cube face), its four tap coordinates and bilinear fractions
-    __shared__ int cpix[SG][IV_H * IV_H];
-    __shared__ int2 ctap[SG][IV_H * IV_H];   // x0 | x1 << 16, y0 | y1 << 16
-    __shared__ float2 cfr[SG][IV_H * IV_H];  // fx, fy
+    using G = IvGeom<SG>;
+    __shared__ int cpix[SG][G::HN];
+    __shared__ int2 ctap[SG][G::HN];   // x0 | x1 << 16, y0 | y1 << 16
+    __shared__ float2 cfr[SG][G::HN];  // fx, fy
     // one slice at a time: the winners' pixel gradients are staged as well
     constexpr bool STAGE_G = SG == 1;
-    __shared__ float cg[STAGE_G ? IV_H * IV_H * TEX_NC(CT) : 1];
+    __shared__ float cg[STAGE_G ? G::HN * TEX_NC(CT) : 1];
     const int Ht = td.Ht, Wt = td.Wt, Ct = CT > 0 ? CT : td.Ct;
     const bool cube = td.kind == DRESSI_TEX_CUBE;
     const int F = tex_faces(td);
@@ -297,20 +305,21 @@ __global__ void __launch_bounds__(IV_T * IV_T)
     const int f = blockIdx.z / nsplit, part = blockIdx.z - f * nsplit;
     const int per = (S + nsplit - 1) / nsplit;
     const int s0 = part * per, s1 = min(S, s0 + per);
-    const int bx0 = blockIdx.x * IV_T, by0 = blockIdx.y * IV_T;
+    const int bx0 = blockIdx.x * IV_T, by0 = blockIdx.y * G::TY;
     const int lx = threadIdx.x % IV_T, ly = threadIdx.x / IV_T;
     const int tx = bx0 + lx, ty = by0 + ly;
     const bool mine = tx < Wt && ty < Ht;
     const int64_t face_cells = (int64_t)Ht * Wt;
     const int64_t cells_all = (int64_t)F * face_cells;
-    // this thread's halo entries (row-major over the 18x18 halo) and their cell offsets
+    // this thread's halo entries (row-major over the halo) and their cell offsets
+    static_assert(G::HN <= 2 * G::NT, "two halo cells per thread");
     int hoff[2];
 #pragma unroll
     for (int k = 0; k < 2; k++) {
-        const int h = threadIdx.x + k * IV_T * IV_T;
+        const int h = threadIdx.x + k * G::NT;
         hoff[k] = -1;
-        if (h < IV_H * IV_H) {
-            int cy = by0 - 1 + h / IV_H, cx = bx0 - 1 + h % IV_H;
+        if (h < G::HN) {
+            int cy = by0 - 1 + h / G::HW, cx = bx0 - 1 + h % G::HW;
             bool ok = true;
             if (wv == DRESSI_WRAP_REPEAT) cy = ((cy % Ht) + Ht) % Ht;
             else ok = cy >= 0 && cy < Ht;
@@ -338,13 +347,16 @@ __global__ void __launch_bounds__(IV_T * IV_T)
         for (int q = 0; q < SG; q++) {
 #pragma unroll
             for (int k = 0; k < 2; k++) {
-                const int h = threadIdx.x + k * IV_T * IV_T;
-                if (h >= IV_H * IV_H) continue;
+                const int h = threadIdx.x + k * G::NT;
+                if (h >= G::HN) continue;
                 int i = wpix[q][k];
                 int2 tp = make_int2(0, 0);
                 float2 fr = make_float2(0.0f, 0.0f);
                 if (i >= 0) {
                     const int64_t o = (int64_t)(g0 + q) * npix + i;
+                    // the winner's gradient is read alongside its coordinate
+                    float g[TEX_NC(CT)];
+                    if constexpr (STAGE_G) ldv<CT>(grad_out + o * Ct, g, Ct);
                     const Taps t = make_taps(td, coord + o * cd, f);
                     if (!t.ok || t.face != f) {
                         i = -1;
@@ -352,8 +364,6 @@ __global__ void __launch_bounds__(IV_T * IV_T)
                         tp = make_int2(t.x0 | (t.x1 << 16), t.y0 | (t.y1 << 16));
                         fr = make_float2(t.fx, t.fy);
                         if constexpr (STAGE_G) {
-                            float g[TEX_NC(CT)];
-                            ldv<CT>(grad_out + o * Ct, g, Ct);
 #pragma unroll
                             for (int c = 0; c < TEX_NC(CT); c++)
                                 if (CT > 0 || c < Ct) cg[h * TEX_NC(CT) + c] = g[c];
@@ -374,7 +384,7 @@ __global__ void __launch_bounds__(IV_T * IV_T)
                 for (int dy = 0; dy < 3; dy++) {
 #pragma unroll
                     for (int dx = 0; dx < 3; dx++) {
-                        const int h = (ly + dy) * IV_H + lx + dx;
+                        const int h = (ly + dy) * G::HW + lx + dx;
                         const int i = cpix[q][h];
                         if (i < 0) continue;
                         const int2 tp = ctap[q][h];
@@ -421,17 +431,18 @@ template <int SG>
 static void launch_gather(int ct, dim3 g, hipStream_t st, const dressi_tex_desc &td, const float *coord,
                           const int32_t *tri_id, int64_t npix, int S, int nsplit, const int32_t *inv,
                           const float *grad_out, float *dst) {
+    constexpr int nt = IvGeom<SG>::NT;
     if (ct == 4)
-        DR_LAUNCH("k_invuv_gather", (k_invuv_gather<4, SG>), g, IV_T * IV_T, 0, st, td, coord, tri_id, npix, S,
+        DR_LAUNCH("k_invuv_gather", (k_invuv_gather<4, SG>), g, nt, 0, st, td, coord, tri_id, npix, S,
                   nsplit, inv, grad_out, dst);
     else if (ct == 3)
-        DR_LAUNCH("k_invuv_gather", (k_invuv_gather<3, SG>), g, IV_T * IV_T, 0, st, td, coord, tri_id, npix, S,
+        DR_LAUNCH("k_invuv_gather", (k_invuv_gather<3, SG>), g, nt, 0, st, td, coord, tri_id, npix, S,
                   nsplit, inv, grad_out, dst);
     else if (ct == 8)
-        DR_LAUNCH("k_invuv_gather", (k_invuv_gather<8, SG>), g, IV_T * IV_T, 0, st, td, coord, tri_id, npix, S,
+        DR_LAUNCH("k_invuv_gather", (k_invuv_gather<8, SG>), g, nt, 0, st, td, coord, tri_id, npix, S,
                   nsplit, inv, grad_out, dst);
     else
-        DR_LAUNCH("k_invuv_gather", (k_invuv_gather<0, SG>), g, IV_T * IV_T, 0, st, td, coord, tri_id, npix, S,
+        DR_LAUNCH("k_invuv_gather", (k_invuv_gather<0, SG>), g, nt, 0, st, td, coord, tri_id, npix, S,
                   nsplit, inv, grad_out, dst);
 }
 
@@ -531,7 +542,8 @@ extern "C" int dressi_texture_bwd(dressi_ctx *ctx, const float *tex, const dress
         nsplit = dressi_invuv_nsplit(cells, S);
         float *dst = grad_tex;
         if (nsplit > 1) dst = part;
-        dim3 g((unsigned)((td->Wt + IV_T - 1) / IV_T), (unsigned)((td->Ht + IV_T - 1) / IV_T),
+        const int ty = S == 1 ? IvGeom<1>::TY : IvGeom<DRESSI_IV_SG>::TY;
+        dim3 g((unsigned)((td->Wt + IV_T - 1) / IV_T), (unsigned)((td->Ht + ty - 1) / ty),
                (unsigned)(tex_faces(*td) * nsplit));
         const int ct = aligned16(grad_out, dst) ? td->Ct : 0;
         if (S == 1) launch_gather<1>(ct, g, st, *td, coord, tri_id, npix, S, nsplit, inv, grad_out, dst);

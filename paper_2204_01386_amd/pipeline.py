@@ -48,7 +48,56 @@ def pack_textures(albedo: np.ndarray, nmap: np.ndarray | None) -> np.ndarray:
     return np.concatenate([albedo, nmap, pad], -1)
 
 
-class Step:
+class _TwoStreams:
+    """With `concurrent` set, independent branches of a step run on a second
+    stream (default priority) with a second library context, so that their
+    scratch never meets the main stream's.  Every fork makes the second stream
+    wait for the main one and every join the reverse, so a step stays one
+    ordered unit on the caller's stream, also when it is captured into a
+    graph.  Without it every call goes to the caller's stream.  Which is
+    faster depends on the workload (cross-stream dependencies cost more than
+    they save on small steps): autotune_streams() times both."""
+
+    concurrent = False
+
+    def _init_streams(self, dev):
+        self.aux = torch.cuda.Stream(device=dev)
+        self.ctx2 = Bd.context_aux(dev.index)
+
+    def _fork(self):
+        if self.concurrent:
+            self.aux.wait_stream(torch.cuda.current_stream())
+
+    def _join(self):
+        if self.concurrent:
+            torch.cuda.current_stream().wait_stream(self.aux)
+
+    def _h2(self):
+        return (self.ctx2 if self.concurrent else self.ctx).handle
+
+    def _sa(self):
+        return C.c_void_p((self.aux if self.concurrent else torch.cuda.current_stream()).cuda_stream)
+
+    def _chk2(self, rc, what):
+        if rc != 0:
+            (self.ctx2 if self.concurrent else self.ctx).check(rc, what)
+
+    def _texture_bwd(self, tex, desc, coord, S, grad_out, grad_tex, grad_coord, what):
+        """Texel gradient (inverse-UV gather) on the second stream and the
+        coordinate gradient on the main one, or both in one call."""
+        H, W = self.H, self.W
+        if not self.concurrent:
+            self._chk(_lib.dressi_texture_bwd(self.ctx.handle, _p(tex), C.byref(desc), _p(coord), _p(self.tri_id),
+                                              S, H, W, _p(grad_out), _p(grad_tex), _p(grad_coord), self._s()), what)
+            return
+        self._fork()
+        self._chk2(_lib.dressi_texture_bwd(self._h2(), _p(tex), C.byref(desc), _p(coord), _p(self.tri_id), S, H, W,
+                                           _p(grad_out), _p(grad_tex), None, self._sa()), what)
+        self._chk(_lib.dressi_texture_bwd(self.ctx.handle, _p(tex), C.byref(desc), _p(coord), _p(self.tri_id), S,
+                                          H, W, _p(grad_out), None, _p(grad_coord), self._s()), what + " coord")
+
+
+class Step(_TwoStreams):
     """Preallocated fwd+bwd of one scene (all views batched in every launch)."""
 
     def __init__(self, scene: Scene, device="cuda", views=None, target: "Step | None" = None,
@@ -146,6 +195,7 @@ class Step:
         self.g_pos_t = e(self.V, 3)
         self.g_pos = e(self.V, 3)
         self.ctx = Bd.context(dev.index)
+        self._init_streams(dev)
         # topology-only structures: built once per mesh
         self.adj = Bd.dressi_adjacency(self.tris, self.V)
         self.uv_adj = Bd.dressi_adjacency(self.uv_tris, self.uv.shape[0]) if self.uv is not None else None
@@ -210,9 +260,17 @@ class Step:
         h, s = self.ctx.handle, self._s()
         B, V, T, H, W, K = self.B, self.V, self.T, self.H, self.W, self.K
         ck = self._chk
-        ck(_lib.dressi_vertex_attrs(h, _p(self.pos), _p(self.tris), V, T, _p(self.extra), _p(self.adj),
-                                    _p(self.vattr), s), "vertex_attrs")
+        h2, sa = self._h2(), self._sa()
+        # vertex attributes beside transform + rasterization
+        self._fork()
+        self._chk2(_lib.dressi_vertex_attrs(h2, _p(self.pos), _p(self.tris), V, T, _p(self.extra), _p(self.adj),
+                                            _p(self.vattr), sa), "vertex_attrs")
         self._raster()
+        self._join()
+        # the backward's fragment index beside the rest of the forward
+        self._fork()
+        self._chk2(_lib.dressi_fragment_index(h2, _p(self.tri_id), B, K, H, W, T, _p(self.frag_index), sa),
+                   "fragment_index")
         ck(_lib.dressi_interpolate(h, _p(self.vattr), 1, V, self.Cv, _p(self.tris), T, _p(self.tri_id),
                                    _p(self.bary), B, K, H, W, _p(self.gbuf), s), "interpolate")
         if self.uv is not None:
@@ -231,6 +289,7 @@ class Step:
         ck(_lib.dressi_softras(h, _p(self.layer_color), _p(self.dist), _p(self.tri_id), B, K, H, W, 3,
                                self.sigma, self.delta, self.blend, _p(self.color), _p(self.sil),
                                _p(self.E), s), "softras")
+        self._join()
 
     def loss_and_grad(self):
         ck = self._chk
@@ -243,8 +302,6 @@ class Step:
         B, V, T, H, W, K = self.B, self.V, self.T, self.H, self.W, self.K
         ck = self._chk
         Cv = self.Cv
-        ck(_lib.dressi_fragment_index(h, _p(self.tri_id), B, K, H, W, T, _p(self.frag_index), s),
-           "fragment_index")
         ck(_lib.dressi_softras_bwd(h, _p(self.layer_color), _p(self.dist), _p(self.tri_id), B, K, H, W, 3,
                                    self.sigma, _p(self.E), _p(self.g_color), _p(self.g_sil),
                                    _p(self.g_layer), _p(self.g_dist), s), "softras_bwd")
@@ -254,9 +311,8 @@ class Step:
             ge.env, ge.env_stride = _cp(self.g_env_s, 0), 3
             ck(_lib.dressi_shade_bwd(h, self.mode, C.byref(self._fin), _p(self.eye), _p(self.tri_id), B,
                                      Npv, _p(self.g_layer), None, C.byref(ge), s), "shade_bwd env")
-            ck(_lib.dressi_texture_bwd(h, _p(self.env), C.byref(self.env_desc), _p(self.dir),
-                                       _p(self.tri_id), B * K, H, W, _p(self.g_env_s), _p(self.g_envtex),
-                                       _p(self.g_dir), s), "texture_bwd env")
+            self._texture_bwd(self.env, self.env_desc, self.dir, B * K, self.g_env_s, self.g_envtex, self.g_dir,
+                              "texture_bwd env")
         g = Bd.FragGrad()
         g.normal, g.normal_stride = _cp(self.g_gbuf, 0), Cv
         g.pos, g.pos_stride = _cp(self.g_gbuf, 3), Cv
@@ -271,9 +327,8 @@ class Step:
                                  _p(self.g_layer), _p(self.g_dir), C.byref(g), s), "shade_bwd")
         gb_in = None
         if self.uv is not None:
-            ck(_lib.dressi_texture_bwd(h, _p(self.tex), C.byref(self.desc), _p(self.uvbuf),
-                                       _p(self.tri_id), B * K, H, W, _p(self.g_samp), _p(self.g_tex),
-                                       _p(self.g_uvbuf), s), "texture_bwd")
+            self._texture_bwd(self.tex, self.desc, self.uvbuf, B * K, self.g_samp, self.g_tex, self.g_uvbuf,
+                              "texture_bwd")
             ck(_lib.dressi_interpolate_bwd(h, _p(self.uv), 1, self.uv.shape[0], 2, _p(self.uv_tris), T,
                                            _p(self.tri_id), _p(self.bary), B, K, H, W, _p(self.g_uvbuf),
                                            None, _p(self.frag_index), _p(self.uv_adj), None,
@@ -292,6 +347,7 @@ class Step:
         ck(_lib.dressi_vertex_attrs_bwd(h, _p(self.pos), _p(self.tris), V, T, Cv, _p(self.adj),
                                         _p(self.g_vattr), _p(self.g_pos_t), _p(self.g_pos), s),
            "vertex_attrs_bwd")
+        self._join()
 
     def run(self):
         """One full step: forward, loss and gradient, backward."""
@@ -355,7 +411,7 @@ def pack_views(sizes, width=None):
     return at, (width, y + shelf)
 
 
-class BatchStep:
+class BatchStep(_TwoStreams):
     """Preallocated fwd+bwd of an uneven batch of standalone scenes (K=1,
     Phong, one 2-D texture each): the meshes are concatenated, every view is
     drawn into its own rectangle of one image and every stage is one launch
@@ -434,6 +490,7 @@ class BatchStep:
         self.g_pos_t = e(self.V, 3)
         self.g_pos = e(self.V, 3)
         self.ctx = Bd.context(dev.index)
+        self._init_streams(dev)
         self.adj = Bd.dressi_adjacency(self.tris, self.V)
         self.uv_adj = Bd.dressi_adjacency(self.uv_tris, self.uv.shape[0])
         nbytes = int(_lib.dressi_fragment_index_bytes(1, 1, H, W, self.T))
@@ -480,9 +537,15 @@ class BatchStep:
     def forward(self):
         h, st = self.ctx.handle, self._s()
         H, W, V, T, ck = self.H, self.W, self.V, self.T, self._chk
-        ck(_lib.dressi_vertex_attrs(h, _p(self.pos), _p(self.tris), V, T, None, _p(self.adj), _p(self.vattr), st),
-           "vertex_attrs")
+        h2, sa = self._h2(), self._sa()
+        self._fork()
+        self._chk2(_lib.dressi_vertex_attrs(h2, _p(self.pos), _p(self.tris), V, T, None, _p(self.adj),
+                                            _p(self.vattr), sa), "vertex_attrs")
         self._raster()
+        self._join()
+        self._fork()
+        self._chk2(_lib.dressi_fragment_index(h2, _p(self.tri_id), 1, 1, H, W, T, _p(self.frag_index), sa),
+                   "fragment_index")
         ck(_lib.dressi_interpolate(h, _p(self.vattr), 1, V, 6, _p(self.tris), T, _p(self.tri_id), _p(self.bary),
                                    1, 1, H, W, _p(self.gbuf), st), "interpolate")
         ck(_lib.dressi_interpolate(h, _p(self.uv), 1, self.uv.shape[0], 2, _p(self.uv_tris), T, _p(self.tri_id),
@@ -493,6 +556,7 @@ class BatchStep:
                              _p(self.layer_color), None, st), "shade")
         ck(_lib.dressi_softras(h, _p(self.layer_color), None, _p(self.tri_id), 1, 1, H, W, 3, 1.0, 0.0,
                                Bd.BLEND_HARD, _p(self.color), _p(self.sil), _p(self.E), st), "softras")
+        self._join()
 
     def loss_and_grad(self):
         self._chk(_lib.dressi_loss_l2(self.ctx.handle, _p(self.color), _p(self.sil), _p(self.target),
@@ -502,7 +566,6 @@ class BatchStep:
     def backward(self):
         h, st = self.ctx.handle, self._s()
         H, W, V, T, ck, Ct = self.H, self.W, self.V, self.T, self._chk, self.Ct
-        ck(_lib.dressi_fragment_index(h, _p(self.tri_id), 1, 1, H, W, T, _p(self.frag_index), st), "fragment_index")
         ck(_lib.dressi_softras_bwd(h, _p(self.layer_color), None, _p(self.tri_id), 1, 1, H, W, 3, 1.0, _p(self.E),
                                    _p(self.g_color), _p(self.g_sil), _p(self.g_layer), None, st), "softras_bwd")
         g = Bd.FragGrad()
@@ -511,8 +574,7 @@ class BatchStep:
         g.albedo, g.albedo_stride = _cp(self.g_samp, 0), Ct
         ck(_lib.dressi_shade_bwd(h, Bd.SHADE_PHONG, C.byref(self._fin), _p(self.eye), _p(self.tri_id), 1, H * W,
                                  _p(self.g_layer), None, C.byref(g), st), "shade_bwd")
-        ck(_lib.dressi_texture_bwd(h, _p(self.tex), C.byref(self.desc), _p(self.uvbuf), _p(self.tri_id), 1, H, W,
-                                   _p(self.g_samp), _p(self.g_tex), _p(self.g_uvbuf), st), "texture_bwd")
+        self._texture_bwd(self.tex, self.desc, self.uvbuf, 1, self.g_samp, self.g_tex, self.g_uvbuf, "texture_bwd")
         ck(_lib.dressi_interpolate_bwd(h, _p(self.uv), 1, self.uv.shape[0], 2, _p(self.uv_tris), T,
                                        _p(self.tri_id), _p(self.bary), 1, 1, H, W, _p(self.g_uvbuf), None,
                                        _p(self.frag_index), _p(self.uv_adj), None, _p(self.g_bary_uv), st),
@@ -528,6 +590,7 @@ class BatchStep:
                                              _p(self.g_pos_t), st), "transform_batched_bwd")
         ck(_lib.dressi_vertex_attrs_bwd(h, _p(self.pos), _p(self.tris), V, T, 6, _p(self.adj), _p(self.g_vattr),
                                         _p(self.g_pos_t), _p(self.g_pos), st), "vertex_attrs_bwd")
+        self._join()
 
     def run(self):
         self.forward()
@@ -610,3 +673,33 @@ def autotune(step, reps: int = 5) -> dict:
             cap <<= 1
         ctx.reserve(0, cap)
     return {"hard_raster": best[0], "hybrid_weight": best[1], "ms": results, "bin_capacity": cap}
+
+
+def autotune_streams(step, reps: int = 20) -> dict:
+    """Chooses between issuing the whole step on the caller's stream and
+    running its independent branches on a second stream, by timing graph
+    replays of the captured step in each mode (the results are the same)."""
+    results = {}
+    for mode in (False, True):
+        step.concurrent = mode
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            step.run()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            step.run()
+        for _ in range(3):
+            g.replay()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            g.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        results[mode] = e0.elapsed_time(e1) / reps
+        del g
+    step.concurrent = min(results, key=results.get)
+    return {"concurrent": step.concurrent, "ms": results}

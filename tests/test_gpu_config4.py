@@ -89,9 +89,16 @@ def test_batch_config4_full_matches_standalone():
     assert_grad_close(host(bs.view_grads(i)["pos"]), o_g["pos"], what="grad pos")
 
 
-def test_batch_deterministic_and_graph_replay(small_batch):
+@pytest.mark.parametrize("concurrent", [False, True])
+def test_batch_deterministic_and_graph_replay(small_batch, concurrent):
+    """Replays of the captured step (on one stream, or with its independent
+    branches on a second stream) give bitwise the eager single-stream step."""
     bs = _batched(small_batch)
     ref = host(bs.g_pos).copy(), host(bs.g_tex).copy()
+    bs.concurrent = concurrent
+    bs.run()
+    torch.cuda.synchronize()
+    assert np.array_equal(host(bs.g_pos), ref[0]) and np.array_equal(host(bs.g_tex), ref[1]), "eager"
     g = torch.cuda.CUDAGraph()
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())

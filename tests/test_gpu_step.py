@@ -186,7 +186,11 @@ def test_step_config3_two_views(B):
     _compare_step(s, views=slice(0, 2), env_tol=2e-2, img_tol=5e-5, kink_tol=True)
 
 
-def test_step_deterministic_and_graph_replay(B):
+@pytest.mark.parametrize("concurrent", [False, True])
+def test_step_deterministic_and_graph_replay(B, concurrent):
+    """The step is bitwise reproducible, also with its independent branches
+    (vertex attributes, fragment index, texel gradients of the texture and
+    the environment map) on a second stream, eager and replayed as a graph."""
     from paper_2204_01386_amd.pipeline import Step, make_target
     s = scenes.config3(n_views=3, subdiv=4, H=128, tex_size=256, env_size=16)
     tgt = make_target(s)
@@ -194,6 +198,7 @@ def test_step_deterministic_and_graph_replay(B):
     st.run()
     torch.cuda.synchronize()
     ref = {k: host(v).copy() for k, v in st.grads().items()}
+    st.concurrent = concurrent
     st.run()
     again = {k: host(v) for k, v in st.grads().items()}
     for k in ref:
