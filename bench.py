@@ -83,8 +83,8 @@ def scene_for(cfg):
 FETCH_SCALE, WRITE_SCALE = 262144.0 / 131083.5, 1.0
 TRAFFIC = {
     "k_invuv_gather": {"src": "paper_2204_01386_amd/csrc/texture.hip",
-                       "sha": "e09cd5301e3a8b8ae5fd794edc23c805990346a36620a5343ae8769289254dfc",
-                       "fetch_kib": 10130.3125, "write_kib": 16384.0},
+                       "sha": "1f4e4c530030523ab6470a293a2ea4a4340887621892495ea96ecad3a7e7d69a",
+                       "fetch_kib": 10126.8125, "write_kib": 16384.0},
 }
 
 
