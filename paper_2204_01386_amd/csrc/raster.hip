@@ -189,14 +189,14 @@ __device__ __forceinline__ void resolve_store(const TriSetup *__restrict__ sv, c
         double E[3];
 #pragma unroll
         for (int i = 0; i < 3; i++) E[i] = dr_edge(s.X, s.Y, i, px, py);
-        // perspective division in double: soft fragments extrapolate and the
-        // sum of l_i/w_i can come close to zero for grazing triangles
-        const double A2 = (double)s.Af;
-        double q0 = ((double)E[0] / A2) / (double)s.w[0];
-        double q1 = ((double)E[1] / A2) / (double)s.w[1];
-        double q2 = ((double)E[2] / A2) / (double)s.w[2];
-        double Q = q0 + q1 + q2;
-        double b0 = q0 / Q, b1 = q1 / Q, b2 = q2 / Q;
+        // perspective-correct b_i = (l_i / w_i) / sum_j (l_j / w_j) with
+        // l_i = E_i / 2A: the area cancels, and multiplying through by
+        // w0 w1 w2 leaves one division.  In double: soft fragments
+        // extrapolate and the sum can come close to zero for grazing triangles.
+        const double w0 = s.w[0], w1 = s.w[1], w2 = s.w[2];
+        const double q0 = E[0] * (w1 * w2), q1 = E[1] * (w0 * w2), q2 = E[2] * (w0 * w1);
+        const double iQ = 1.0 / (q0 + q1 + q2);
+        double b0 = q0 * iQ, b1 = q1 * iQ, b2 = q2 * iQ;
         bool swapped = dr_corner(s.meta, 1) == 2;
         tri_id[o] = t;
         bary[o] = make_float2((float)b0, (float)(swapped ? b2 : b1));

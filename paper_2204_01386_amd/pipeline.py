@@ -391,12 +391,21 @@ def make_target(scene: Scene, device="cuda", views=None) -> Step:
 # ---------------------------------------------------------------------------
 def pack_views(sizes, width=None):
     """Shelf packing of views (W_i, H_i) into one image: views sorted by
-    height (then width, then index) fill rows left to right.  Returns the
-    (x0, y0) of every view and the image size (Wc, Hc)."""
+    height (then width, then index) fill rows left to right.  Without a
+    width, every multiple of 256 from the widest view up to four times the
+    side of a square of the same area is tried and the smallest image kept
+    (the narrower on ties).  Returns the (x0, y0) of every view and the image
+    size (Wc, Hc)."""
     n = len(sizes)
-    area = sum(w * h for w, h in sizes)
     if width is None:
-        width = max(max(w for w, _ in sizes), int(math.ceil(math.sqrt(1.25 * area) / 256.0)) * 256)
+        area = sum(w * h for w, h in sizes)
+        w0 = max(w for w, _ in sizes)
+        best = None
+        for wd in range(int(math.ceil(w0 / 256.0)) * 256, max(w0, int(4 * math.sqrt(area))) + 256, 256):
+            _, (wc, hc) = pack_views(sizes, wd)
+            if best is None or wc * hc < best[0]:
+                best = (wc * hc, wd)
+        width = max(w0, best[1])
     order = sorted(range(n), key=lambda i: (-sizes[i][1], -sizes[i][0], i))
     x = y = shelf = 0
     at = [None] * n
