@@ -62,9 +62,10 @@ bool dr_prof_slot(const char *name, hipEvent_t *start, hipEvent_t *stop);
 // Inverse-UV gather: slices whose cell halos are loaded together, and the
 // split of the slices over the grid for small textures (with its scratch of
 // partial sums).
-#define DRESSI_IV_SG 4
+#define DRESSI_IV_SG 1     // slices staged together by the inverse-UV gather
+#define DRESSI_IV_PART 4   // slices per part when a small texture's slices are split over the grid
 static inline int dressi_invuv_nsplit(int64_t cells, int S) {
-    return (cells < (1 << 19) && S > DRESSI_IV_SG) ? (S + DRESSI_IV_SG - 1) / DRESSI_IV_SG : 1;
+    return (cells < (1 << 19) && S > DRESSI_IV_PART) ? (S + DRESSI_IV_PART - 1) / DRESSI_IV_PART : 1;
 }
 static inline size_t dressi_invuv_part_bytes(int64_t cells, int Ct, int S) {
     int ns = dressi_invuv_nsplit(cells, S);

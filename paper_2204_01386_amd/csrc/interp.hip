@@ -168,7 +168,7 @@ __global__ void k_interp_bwd_bary(const float *__restrict__ attr, int Ba, int Va
 }
 
 // Row of C floats; CC = C at compile time (0: run time), 8-byte aligned rows
-// with an even CC are read in pairs.
+// with an even CC are read in pairs, odd ones one float at a time.
 template <int CC>
 __device__ __forceinline__ void ld_row(const float *src, float *v, int C) {
     if constexpr (CC > 0 && (CC & 1) == 0) {
@@ -387,6 +387,9 @@ extern "C" int dressi_interpolate_bwd(dressi_ctx *ctx, const float *attr, int Ba
                           Va, C, attr_tris, T, tri_id, b2, K, H, W, ntx, nt, fl, grad_out, gbi, gbo, part);
             else if (al8 && C == 2)
                 DR_LAUNCH("k_interp_bwd_tile", (k_interp_bwd_tile<2>), B * nt, DRESSI_TILE_PIX, lds, st, attr, Ba,
+                          Va, C, attr_tris, T, tri_id, b2, K, H, W, ntx, nt, fl, grad_out, gbi, gbo, part);
+            else if (C == 9)
+                DR_LAUNCH("k_interp_bwd_tile", (k_interp_bwd_tile<9>), B * nt, DRESSI_TILE_PIX, lds, st, attr, Ba,
                           Va, C, attr_tris, T, tri_id, b2, K, H, W, ntx, nt, fl, grad_out, gbi, gbo, part);
             else
                 DR_LAUNCH("k_interp_bwd_tile", (k_interp_bwd_tile<0>), B * nt, DRESSI_TILE_PIX, lds, st, attr, Ba,

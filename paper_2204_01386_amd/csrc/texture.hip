@@ -259,7 +259,7 @@ __global__ void __launch_bounds__(256)
 }
 
 // Texture gradient through the inverse UV.  One block of texels (16 columns,
-// 32 rows for a single slice, else 16) per workgroup: per slice the cells
+// 32 rows when one slice is staged at a time, else 16) per workgroup: per slice the cells
 // around the block (a one-cell halo) are staged in LDS
 // (wrapped, or -1 outside a clamped texture); blocks whose cells are all
 // empty skip the slice.  Each texel then visits its 3x3 cells in row-major
@@ -269,12 +269,13 @@ __global__ void __launch_bounds__(256)
 // Per texel: the sum over slices [s0, s1), in ascending order, of the distinct
 // in-range cells of its 3x3 block, row-major, of the winner pixel's bilinear
 // weight on this texel times its gradient.  A block of texels loads the
-// haloed cells of DRESSI_IV_SG slices at once (all loads in flight), skips the
+// haloed cells of SG slices at once (all loads in flight), skips the
 // group when every cell is empty, then gathers.  With nsplit > 1 the slice
 // range is split over grid.z and each part writes its own partial sum.  SG
-// slices are staged at a time (SG = 1 for a single slice keeps the LDS small
-// and the occupancy high).  A winner found in a cell of face or layer f has
-// its taps on f, so they are recomputed from its coordinate alone.
+// slices (DRESSI_IV_SG) are staged at a time, with each winner's taps and
+// gradient, so the texel loop reads LDS only.  A
+// winner found in a cell of face or layer f has its taps on f, so they are
+// recomputed from its coordinate alone.
 template <int SG>
 struct IvGeom {
     static constexpr int TY = SG == 1 ? 32 : 16;   // texel rows per block (16 columns)
@@ -293,9 +294,8 @@ __global__ void __launch_bounds__(IvGeom<SG>::NT)
     __shared__ int cpix[SG][G::HN];
     __shared__ int2 ctap[SG][G::HN];   // x0 | x1 << 16, y0 | y1 << 16
     __shared__ float2 cfr[SG][G::HN];  // fx, fy
-    // one slice at a time: the winners' pixel gradients are staged as well
-    constexpr bool STAGE_G = SG == 1;
-    __shared__ float cg[STAGE_G ? G::HN * TEX_NC(CT) : 1];
+    // the winners' pixel gradients are staged as well
+    __shared__ float cg[SG][G::HN * TEX_NC(CT)];
     const int Ht = td.Ht, Wt = td.Wt, Ct = CT > 0 ? CT : td.Ct;
     const bool cube = td.kind == DRESSI_TEX_CUBE;
     const int F = tex_faces(td);
@@ -356,18 +356,16 @@ __global__ void __launch_bounds__(IvGeom<SG>::NT)
                     const int64_t o = (int64_t)(g0 + q) * npix + i;
                     // the winner's gradient is read alongside its coordinate
                     float g[TEX_NC(CT)];
-                    if constexpr (STAGE_G) ldv<CT>(grad_out + o * Ct, g, Ct);
+                    ldv<CT>(grad_out + o * Ct, g, Ct);
                     const Taps t = make_taps(td, coord + o * cd, f);
                     if (!t.ok || t.face != f) {
                         i = -1;
                     } else {
                         tp = make_int2(t.x0 | (t.x1 << 16), t.y0 | (t.y1 << 16));
                         fr = make_float2(t.fx, t.fy);
-                        if constexpr (STAGE_G) {
 #pragma unroll
-                            for (int c = 0; c < TEX_NC(CT); c++)
-                                if (CT > 0 || c < Ct) cg[h * TEX_NC(CT) + c] = g[c];
-                        }
+                        for (int c = 0; c < TEX_NC(CT); c++)
+                            if (CT > 0 || c < Ct) cg[q][h * TEX_NC(CT) + c] = g[c];
                     }
                 }
                 cpix[q][h] = i;
@@ -379,7 +377,6 @@ __global__ void __launch_bounds__(IvGeom<SG>::NT)
         if (!__syncthreads_or(found)) continue;
         if (mine) {
             for (int q = 0; q < ng; q++) {
-                const int s = g0 + q;
 #pragma unroll
                 for (int dy = 0; dy < 3; dy++) {
 #pragma unroll
@@ -397,13 +394,9 @@ __global__ void __launch_bounds__(IvGeom<SG>::NT)
                         if (y1 == ty && x1 == tx) w += fr.y * fr.x;
                         if (w == 0.0f) continue;
                         float g[TEX_NC(CT)];
-                        if constexpr (STAGE_G) {
 #pragma unroll
-                            for (int c = 0; c < TEX_NC(CT); c++)
-                                if (CT > 0 || c < Ct) g[c] = cg[h * TEX_NC(CT) + c];
-                        } else {
-                            ldv<CT>(grad_out + ((int64_t)s * npix + i) * Ct, g, Ct);
-                        }
+                        for (int c = 0; c < TEX_NC(CT); c++)
+                            if (CT > 0 || c < Ct) g[c] = cg[q][h * TEX_NC(CT) + c];
 #pragma unroll
                         for (int c = 0; c < TEX_NC(CT); c++)
                             if (CT > 0 || c < Ct) acc[c] += w * g[c];
@@ -542,12 +535,11 @@ extern "C" int dressi_texture_bwd(dressi_ctx *ctx, const float *tex, const dress
         nsplit = dressi_invuv_nsplit(cells, S);
         float *dst = grad_tex;
         if (nsplit > 1) dst = part;
-        const int ty = S == 1 ? IvGeom<1>::TY : IvGeom<DRESSI_IV_SG>::TY;
+        const int ty = IvGeom<DRESSI_IV_SG>::TY;
         dim3 g((unsigned)((td->Wt + IV_T - 1) / IV_T), (unsigned)((td->Ht + ty - 1) / ty),
                (unsigned)(tex_faces(*td) * nsplit));
         const int ct = aligned16(grad_out, dst) ? td->Ct : 0;
-        if (S == 1) launch_gather<1>(ct, g, st, *td, coord, tri_id, npix, S, nsplit, inv, grad_out, dst);
-        else launch_gather<DRESSI_IV_SG>(ct, g, st, *td, coord, tri_id, npix, S, nsplit, inv, grad_out, dst);
+        launch_gather<DRESSI_IV_SG>(ct, g, st, *td, coord, tri_id, npix, S, nsplit, inv, grad_out, dst);
         if (nsplit > 1) {
             int64_t ne = cells * td->Ct;
             DR_LAUNCH("k_invuv_reduce", (k_invuv_reduce), (int)((ne + 255) / 256), 256, 0, st, part, nsplit, ne,

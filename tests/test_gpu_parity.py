@@ -235,7 +235,7 @@ def test_raster_status_clean(B):
 # ---------------------------------------------------------------------------
 # interpolate
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("C,Ba", [(6, 1), (11, 1), (20, 2), (3, 2), (40, 1), (2, 1)])
+@pytest.mark.parametrize("C,Ba", [(6, 1), (11, 1), (20, 2), (3, 2), (40, 1), (2, 1), (9, 2)])
 def test_interpolate(B, C, Ba):
     pc, tris = sphere_scene(subdiv=3, views=2, seed=1)
     H, W, K = 72, 90, 2
