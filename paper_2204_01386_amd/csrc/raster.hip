@@ -356,20 +356,30 @@ __device__ __forceinline__ float rl_segmin_i(const int *qx, const int *qy, const
 
 // Merges the candidate fragment of triangle t at this lane's pixel.  MAYHARD
 // is false when no pixel centre of the wavefront can be inside the triangle.
+// Edge vectors of the 32-bit path: edge i (opposite vertex i) runs from
+// vertex i+1 to vertex i+2 (mod 3); every component is below 2^15 there.
+__device__ __forceinline__ void rl_edges(const TriSetup &s, int *ex, int *ey) {
+#pragma unroll
+    for (int i = 0; i < 3; i++) {
+        const int a = (i + 1) % 3, c = (i + 2) % 3;
+        ex[i] = s.X[c] - s.X[a];
+        ey[i] = s.Y[c] - s.Y[a];
+    }
+}
+
 // One staged triangle (slot e of the batch) rasterized over its pixels in the
 // tile, hard fragments only, merged into the tile's per-pixel slots: the same
 // edge values (32-bit or exact double), depth and key as rl_merge.
-__device__ __forceinline__ void rl_tri_in_tile(int e, const int *sid, const int *sflag, const int2 *sbox,
-                                               const int4 *sxy0, const int2 *sxy1, const float4 *sz,
-                                               const int4 *sed, int tx, int ty,
-                                               unsigned long long *slot) {
-    const int fl = sflag[e];
+__device__ __forceinline__ void rl_tri_in_tile(int e, const int2 *sfi, const int2 *sbox,
+                                               const int4 *sxy0, const int2 *sxy1, const float4 *sz, int tx,
+                                               int ty, unsigned long long *slot) {
+    const int fl = sfi[e].x;
     if (!(fl & 1)) return;
     const int2 bx = sbox[e];
     const int x0 = max(bx.x & 0xffff, tx * DRESSI_TILE), x1 = min(bx.x >> 16, tx * DRESSI_TILE + DRESSI_TILE - 1);
     const int y0 = max(bx.y & 0xffff, ty * DRESSI_TILE), y1 = min(bx.y >> 16, ty * DRESSI_TILE + DRESSI_TILE - 1);
     if (x0 > x1 || y0 > y1) return;
-    const int t = sid[e];
+    const int t = sfi[e].y;
     const int4 q0 = sxy0[e];
     const int2 q1 = sxy1[e];
     const float4 z4 = sz[e];
@@ -382,11 +392,7 @@ __device__ __forceinline__ void rl_tri_in_tile(int e, const int *sid, const int 
     const bool own0 = (s.meta >> 1) & 1, own1 = (s.meta >> 2) & 1, own2 = (s.meta >> 3) & 1;
     const bool small = fl >> 16;
     int ex[3], ey[3];
-    {
-        const int4 ed = sed[e];
-        ex[0] = lo16(ed.x); ex[1] = lo16(ed.y); ex[2] = lo16(ed.z);
-        ey[0] = hi16(ed.x); ey[1] = hi16(ed.y); ey[2] = hi16(ed.z);
-    }
+    rl_edges(s, ex, ey);
     for (int y = y0; y <= y1; y++) {
         const int py = DRESSI_SUBPIX * y + DRESSI_SUBPIX / 2;
         for (int x = x0; x <= x1; x++) {
@@ -515,14 +521,13 @@ __device__ __forceinline__ int wave_max_i(int v) {
 }
 
 template <int K, bool SOFT, bool HYB = false>
-__global__ void __launch_bounds__(DRESSI_TILE_PIX) __attribute__((amdgpu_waves_per_eu(5)))
+__global__ void __launch_bounds__(DRESSI_TILE_PIX) __attribute__((amdgpu_waves_per_eu(SOFT ? 6 : 5)))
     k_raster_list(const TriSetup *__restrict__ setup, int32_t *__restrict__ counts,
                   const int32_t *__restrict__ bins, int cap, int T, int H, int W, int ntx, int nt,
                   float r, int32_t *__restrict__ tri_id, float2 *__restrict__ bary,
                   float *__restrict__ dist, int hyb_w) {
     // staged triangles (structure of arrays)
-    __shared__ int sid[RL_BATCH];       // triangle id
-    __shared__ int sflag[RL_BATCH];     // meta | float-exact flag << 16
+    __shared__ int2 sfi[RL_BATCH];      // meta | 32-bit-exact flag << 16, triangle id
     __shared__ int2 sbox[RL_BATCH];     // soft box
     __shared__ int2 shb[RL_BATCH];      // pixels with centres in the vertex box
     __shared__ int szlb[RL_BATCH];      // lower bound of the hard keys (float bits)
@@ -530,8 +535,6 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX) __attribute__((amdgpu_waves_p
     __shared__ int4 sxy0[RL_BATCH];     // X0 X1 X2 Y0
     __shared__ int2 sxy1[RL_BATCH];     // Y1 Y2
     __shared__ float4 sz[RL_BATCH];     // zn0 zn1 zn2 Af
-    __shared__ int4 sed[RL_BATCH];      // edge vectors (ex | ey << 16) of the 32-bit path
-    __shared__ int4 slen[RL_BATCH];     // their squared lengths
     // triangle-parallel batches (HYB): per-pixel slot and the batch costs,
     // double-buffered by batch parity
     __shared__ unsigned long long sslot[HYB ? DRESSI_TILE_PIX : 1];
@@ -591,7 +594,6 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX) __attribute__((amdgpu_waves_p
                     // tile and every edge vector below 2^15 in magnitude
                     const int lim15 = 1 << 15, span = DRESSI_SUBPIX * (DRESSI_TILE - 1);
                     bool small = true;
-                    int exy[3], l2[3];
 #pragma unroll
                     for (int i = 0; i < 3; i++) {
                         small = small && abs(px0 - s.X[i]) < lim15 && abs(px0 + span - s.X[i]) < lim15 &&
@@ -599,14 +601,9 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX) __attribute__((amdgpu_waves_p
                         const int a = (i + 1) % 3, c = (i + 2) % 3;
                         const int ex = s.X[c] - s.X[a], ey = s.Y[c] - s.Y[a];
                         small = small && abs(ex) < lim15 && abs(ey) < lim15;
-                        exy[i] = (ex & 0xffff) | (ey << 16);
-                        l2[i] = small ? ex * ex + ey * ey : 0;
                     }
-                    sed[p] = make_int4(exy[0], exy[1], exy[2], 0);
                     sel[p] = make_float4(s.elen[0], s.elen[1], s.elen[2], 0.0f);
-                    slen[p] = make_int4(l2[0], l2[1], l2[2], 0);
-                    sid[p] = t;
-                    sflag[p] = (s.meta & 0xffff) | (small ? 0x10000 : 0);
+                    sfi[p] = make_int2((s.meta & 0xffff) | (small ? 0x10000 : 0), t);
                     sbox[p] = make_int2(s.box0, s.box1);
                     shb[p] = make_int2(s.hbox0, s.hbox1);
                     szlb[p] = s.zlb;
@@ -636,7 +633,7 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX) __attribute__((amdgpu_waves_p
             }
             if (HYB) use_tp = 16 * scost[par][0] < hyb_w * scost[par][1];
             if (HYB && use_tp) {
-                if (p < n) rl_tri_in_tile(p, sid, sflag, sbox, sxy0, sxy1, sz, sed, tx, ty, sslot);
+                if (p < n) rl_tri_in_tile(p, sfi, sbox, sxy0, sxy1, sz, tx, ty, sslot);
                 continue;
             }
             for (int c = 0; c < n; c += 64) {
@@ -659,8 +656,8 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX) __attribute__((amdgpu_waves_p
                 while (todo) {
                     const int j = c + __ffsll((long long)todo) - 1;
                     todo &= todo - 1ull;
-                    const int fl = sflag[j];
-                    const int t = sid[j];
+                    const int2 fi = sfi[j];
+                    const int fl = fi.x, t = fi.y;
                     const float4 e4 = sel[j];
                     const int4 q0 = sxy0[j];
                     const int2 q1 = sxy1[j];
@@ -674,11 +671,10 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX) __attribute__((amdgpu_waves_p
                     const float el[3] = {e4.x, e4.y, e4.z};
                     if (fl >> 16) {
                         // exact in 32-bit integers (see the staging test)
-                        const int4 ed = sed[j];
-                        const int4 ln = slen[j];
-                        const int ex[3] = {lo16(ed.x), lo16(ed.y), lo16(ed.z)};
-                        const int ey[3] = {hi16(ed.x), hi16(ed.y), hi16(ed.z)};
-                        const int len2[3] = {ln.x, ln.y, ln.z};
+                        int ex[3], ey[3], len2[3];
+                        rl_edges(s, ex, ey);
+#pragma unroll
+                        for (int i = 0; i < 3; i++) len2[i] = __mul24(ex[i], ex[i]) + __mul24(ey[i], ey[i]);
                         int qx[3], qy[3], E[3];
 #pragma unroll
                         for (int v = 0; v < 3; v++) {
