@@ -521,7 +521,7 @@ __device__ __forceinline__ int wave_max_i(int v) {
 }
 
 template <int K, bool SOFT, bool HYB = false>
-__global__ void __launch_bounds__(DRESSI_TILE_PIX) __attribute__((amdgpu_waves_per_eu(SOFT ? 6 : 5)))
+__global__ void __launch_bounds__(DRESSI_TILE_PIX) __attribute__((amdgpu_waves_per_eu(SOFT ? 7 : 5)))
     k_raster_list(const TriSetup *__restrict__ setup, int32_t *__restrict__ counts,
                   const int32_t *__restrict__ bins, int cap, int T, int H, int W, int ntx, int nt,
                   float r, int32_t *__restrict__ tri_id, float2 *__restrict__ bary,
