@@ -331,16 +331,28 @@ __global__ void __launch_bounds__(IvGeom<SG>::NT)
     float acc[TEX_NC(CT)];
 #pragma unroll
     for (int c = 0; c < TEX_NC(CT); c++) acc[c] = 0.0f;
-    for (int g0 = s0; g0 < s1; g0 += SG) {
+    // winners of a group's halo cells; the next group's are loaded while the
+    // current one is processed
+    auto load_group = [&](int g0, int (*w)[2]) {
         const int ng = min(SG, s1 - g0);
-        // winners of the group's halo cells (all loads in flight)
-        int wpix[SG][2];
 #pragma unroll
         for (int q = 0; q < SG; q++) {
             const int32_t *iv = inv + (int64_t)(g0 + q) * cells_all + (int64_t)f * face_cells;
 #pragma unroll
-            for (int k = 0; k < 2; k++) wpix[q][k] = (q < ng && hoff[k] >= 0) ? iv[hoff[k]] : -1;
+            for (int k = 0; k < 2; k++) w[q][k] = (q < ng && hoff[k] >= 0) ? iv[hoff[k]] : -1;
         }
+    };
+    int wnext[SG][2];
+    if (s0 < s1) load_group(s0, wnext);
+    for (int g0 = s0; g0 < s1; g0 += SG) {
+        const int ng = min(SG, s1 - g0);
+        int wpix[SG][2];
+#pragma unroll
+        for (int q = 0; q < SG; q++) {
+            wpix[q][0] = wnext[q][0];
+            wpix[q][1] = wnext[q][1];
+        }
+        if (g0 + SG < s1) load_group(g0 + SG, wnext);
         int found = 0;
         // each winner's taps, computed once for the up to 9 texels that visit it
 #pragma unroll
