@@ -136,6 +136,17 @@ size_t dressi_fragindex_tmp_bytes(int B, int T);
 void dressi_build_fragindex(const int32_t *tri_id, int B, int K, int H, int W, int T, void *base,
                             void *tmp, int32_t *zero_counts, hipStream_t s);
 
+// MI355X dispatches the workgroups of a grid to its 8 XCDs round-robin
+// (workgroup i on XCD i mod 8), and each XCD has its own L2.  The logical
+// block index below gives every XCD one contiguous range of the grid, so
+// workgroups that touch neighbouring pixels or tiles (and share triangles,
+// attributes and texels) run behind the same L2.  A bijection of [0, nb).
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb) {
+    const int64_t q = nb >> 3, r = nb & 7, x = b & 7;
+    return x * q + (x < r ? x : r) + (b >> 3);
+}
+__device__ __forceinline__ int64_t xcd_block() { return xcd_block(blockIdx.x, gridDim.x); }
+
 __host__ __device__ static inline int tiles_x(int W) { return (W + DRESSI_TILE - 1) / DRESSI_TILE; }
 __host__ __device__ static inline int tiles_y(int H) { return (H + DRESSI_TILE - 1) / DRESSI_TILE; }
 

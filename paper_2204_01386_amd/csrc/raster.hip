@@ -216,7 +216,7 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX)
              float *__restrict__ dist) {
     __shared__ unsigned long long slot[DRESSI_TILE_PIX];
     __shared__ float prev[DRESSI_TILE_PIX];
-    const int bt = blockIdx.x;
+    const int bt = (int)xcd_block();
     const int b = bt / nt, tile = bt - b * nt;
     const int tx = tile % ntx, ty = tile / ntx;
     const int p = threadIdx.x;
@@ -540,7 +540,7 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX) __attribute__((amdgpu_waves_p
     __shared__ unsigned long long sslot[HYB ? DRESSI_TILE_PIX : 1];
     __shared__ int scost[2][2];
     static_assert(!HYB || (K == 1 && !SOFT), "the hybrid strategy is for one hard layer");
-    const int bt = blockIdx.x;
+    const int bt = (int)xcd_block();
     const int b = bt / nt, tile = bt - b * nt;
     const int tx = tile % ntx, ty = tile / ntx;
     const int p = threadIdx.x;
