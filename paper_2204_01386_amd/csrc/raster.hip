@@ -283,9 +283,13 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX)
 //    its vertex box and the strip) is above every lane's current K-th key;
 //  * per lane, a soft candidate is dropped before its segment distances when
 //    the line distance of an edge it lies outside of already rules it out.
-// Edge functions are evaluated in float with two FMAs per edge when staging
-// has shown that every value over the tile is an integer below 2^24 (then the
-// float result is exact); otherwise in the exact double form.
+// Edge functions (and the segment-distance products) are evaluated with
+// 24-bit integer multiplies when staging has shown that every pixel-to-vertex
+// difference over the tile and every edge vector is below 2^15 in magnitude
+// (then every product and sum of two products fits in 32 bits, exactly);
+// otherwise in the exact double form.  Workgroups take the tiles in an
+// XCD-aware order (each XCD one contiguous range), so the setup records of
+// neighbouring tiles are read through one L2.
 // ---------------------------------------------------------------------------
 #define RL_BATCH 256
 #define RL_NEAR 2

@@ -232,6 +232,20 @@ def test_raster_status_clean(B):
     assert ctx.check_status() == 0
 
 
+def test_tune_rejects_bad_values(B):
+    """The tuning knobs accept only their documented ranges and leave the
+    context usable (a rejected value changes nothing)."""
+    ctx = B.Context(torch.cuda.current_device())
+    bad = [(B.TUNE_HARD_RASTER, -1), (B.TUNE_HARD_RASTER, 3), (B.TUNE_HYBRID_WEIGHT, 0),
+           (B.TUNE_HYBRID_WEIGHT, 1025), (B.TUNE_BIN_CAPACITY, -1), (B.TUNE_BIN_CAPACITY, (1 << 26) + 1), (99, 1)]
+    for key, value in bad:
+        with pytest.raises(B.DressiError, match="EINVAL"):
+            ctx.tune(key, value)
+    for key, value in [(B.TUNE_HARD_RASTER, 2), (B.TUNE_HYBRID_WEIGHT, 1), (B.TUNE_HYBRID_WEIGHT, 1024),
+                       (B.TUNE_BIN_CAPACITY, 0)]:
+        ctx.tune(key, value)
+
+
 # ---------------------------------------------------------------------------
 # interpolate
 # ---------------------------------------------------------------------------
