@@ -200,7 +200,9 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX)
                       float2 *__restrict__ grad_bary, float *__restrict__ partial) {
     extern __shared__ float vals[];   // [K*256][ib_stride(C)]
     if (CC > 0) C = CC;
-    const int bt = blockIdx.x;
+    // several views: XCD-aware order (each XCD whole views); one view keeps the
+    // default interleave, which balances uneven work over the image
+    const int bt = (int)gridDim.x > nt ? (int)xcd_block() : (int)blockIdx.x;
     const int b = bt / nt, tile = bt - b * nt;
     const int tx = tile % ntx, ty = tile / ntx;
     const int p = threadIdx.x;

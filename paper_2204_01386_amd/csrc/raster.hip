@@ -910,7 +910,9 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX)
     __shared__ unsigned long long runs[DRESSI_MAX_K * DRESSI_TILE_PIX];
     __shared__ unsigned long long keys[DRESSI_MAX_K * DRESSI_TILE_PIX];
     __shared__ int wsum[DRESSI_TILE_PIX / 64];
-    const int bt = blockIdx.x;
+    // several views: XCD-aware order (each XCD whole views); one view keeps the
+    // default interleave, which balances uneven work over the image
+    const int bt = (int)gridDim.x > nt ? (int)xcd_block() : (int)blockIdx.x;
     const int b = bt / nt, tile = bt - b * nt;
     const int tx = tile % ntx, ty = tile / ntx;
     const int p = threadIdx.x;
@@ -1042,7 +1044,9 @@ void dressi_fragindex_view(void *base, int B, int K, int H, int W, int T, FragLi
 // ---------------------------------------------------------------------------
 __global__ void k_tt_fill(FragLists fl, int K, int T, int nt, const int32_t *__restrict__ offsets,
                           int32_t *__restrict__ counts, int2 *__restrict__ entries) {
-    const int bt = blockIdx.x;
+    // several views: XCD-aware order (each XCD whole views); one view keeps the
+    // default interleave, which balances uneven work over the image
+    const int bt = (int)gridDim.x > nt ? (int)xcd_block() : (int)blockIdx.x;
     const int b = bt / nt;
     const int64_t base = (int64_t)bt * DRESSI_TILE_PIX * K;
     const int n = fl.n_rec[bt];
@@ -1235,7 +1239,9 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX)
                     FragLists fl, int ntx, int nt, const float2 *__restrict__ grad_bary,
                     const float *__restrict__ grad_dist, float *__restrict__ partial) {
     extern __shared__ float vals[];   // [K*256][9]
-    const int bt = blockIdx.x;
+    // several views: XCD-aware order (each XCD whole views); one view keeps the
+    // default interleave, which balances uneven work over the image
+    const int bt = (int)gridDim.x > nt ? (int)xcd_block() : (int)blockIdx.x;
     const int nf = fl.n_frag[bt];
     if (nf == 0) return;
     const int b = bt / nt, tile = bt - b * nt;
