@@ -28,7 +28,7 @@ _lib = Bd._lib
 # per-tile hard rasterization: cost of a pixel-parallel triangle step over a
 # triangle-parallel pixel step, in sixteenths; the autotuner tries these
 HYBRID_WEIGHT_DEFAULT = 24
-HYBRID_WEIGHTS = (12, 16, 24, 40)
+HYBRID_WEIGHTS = (6, 9, 12, 16, 24, 40)
 
 
 def _p(t):
