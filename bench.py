@@ -83,8 +83,8 @@ def scene_for(cfg):
 FETCH_SCALE, WRITE_SCALE = 262144.0 / 131083.5, 1.0
 TRAFFIC = {
     "k_invuv_gather": {"src": "paper_2204_01386_amd/csrc/texture.hip",
-                       "sha": "1f4e4c530030523ab6470a293a2ea4a4340887621892495ea96ecad3a7e7d69a",
-                       "fetch_kib": 10126.8125, "write_kib": 16384.0},
+                       "sha": "bc91292cd3498bb52e427b69242e1fb08a67f7aa1dc642d48e410b752cccce48",
+                       "fetch_kib": 10128.3125, "write_kib": 16384.0},
 }
 
 

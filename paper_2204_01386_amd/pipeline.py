@@ -61,8 +61,15 @@ class _TwoStreams:
     concurrent = False
 
     def _init_streams(self, dev):
-        self.aux = torch.cuda.Stream(device=dev)
+        self._aux = None
         self.ctx2 = Bd.context_aux(dev.index)
+
+    @property
+    def aux(self):
+        """The second stream, created on first use."""
+        if self._aux is None:
+            self._aux = torch.cuda.Stream(device=self.dev)
+        return self._aux
 
     def _fork(self):
         if self.concurrent:
