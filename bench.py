@@ -58,7 +58,35 @@ def parse():
     ap.add_argument("--uneven-steps", type=int, default=20)
     ap.add_argument("--copy-ref", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of MIB MiB (reference for HBM counters)")
+    ap.add_argument("--paper-table", action="store_true",
+                    help="instead: fwd+bwd time per view on workloads shaped like the paper's non-textured "
+                         "timing table (windows 256^2-2048^2, three mesh sizes, six views, white Lambert)")
     return ap.parse_args()
+
+
+# The paper's non-textured fwd+bwd time per view (ms) on one RTX 2080 (§5.1
+# table), by window and by mesh (682, 14,208 and 51,414 triangles).
+PAPER_TABLE_MS = {256: (0.304, 0.308, 0.364), 512: (0.442, 0.480, 0.502), 1024: (1.034, 1.106, 1.104),
+                  2048: (3.301, 3.545, 3.469)}
+PAPER_TABLE_TRIS = (682, 14208, 51414)
+
+
+def paper_table(steps, warmup):
+    """Each cell: six views of one mesh rendered and differentiated as one
+    graph-captured step; time per view = step time / 6."""
+    from paper_2204_01386_amd import scenes
+    rows = []
+    for H, paper_ms in PAPER_TABLE_MS.items():
+        for T, pm in zip(PAPER_TABLE_TRIS, paper_ms):
+            sc = scenes.paper_table_scene(T, H)
+            m = measure(sc, steps, warmup, -1)
+            per_view = m["ms_per_step"] / sc.mvp.shape[0]
+            rows.append({"window": H, "triangles": int(sc.tris.shape[0]), "paper_triangles": T,
+                         "views": int(sc.mvp.shape[0]), "ms_per_view": round(per_view, 4),
+                         "Mpix_s": round(H * H / (per_view * 1e-3) / 1e6, 1),
+                         "paper_ms_per_view": pm, "paper_hardware": "NVIDIA GeForce RTX 2080"})
+            del m
+    return rows
 
 
 def scene_for(cfg):
@@ -459,6 +487,10 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.paper_table:
+        print(json.dumps({"paper_table": paper_table(min(args.steps, 50), min(args.warmup, 5)),
+                          "note": "white Lambert spheres here, silhouette shading in the paper; context only"}))
+        return
     if args.copy_ref:
         src = torch.ones(args.copy_ref * (1 << 18), dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)

@@ -525,6 +525,22 @@ def config5(seed: int = 0, n_views: int = 8, H: int = 2048, nu: int = 2048, nv: 
     return s
 
 
+def paper_table_scene(triangles: int, H: int, n_views: int = 6, seed: int = 0) -> Scene:
+    """A workload shaped like the paper's non-textured timing table (§5.1):
+    a noisy latitude-longitude sphere with about `triangles` triangles
+    (2 nu nv with nu = 2 nv), white vertex colour, Lambert, K = 1, seen by
+    `n_views` cameras on the ring of config 3 at H x H; target: positions +
+    N(0, 0.02)."""
+    nv = max(3, int(round(math.sqrt(triangles / 4.0))))
+    p, tris, _, _ = uv_sphere(2 * nv, nv, seed)
+    white = np.ones((len(p), 3), np.float32)
+    trng = np.random.default_rng([seed, 1])
+    tpos = (p + trng.normal(0.0, 0.02, p.shape)).astype(np.float32)
+    eyes = camera_ring(n_views, seed)
+    return Scene(f"paper-table-{len(tris)}-{H}", p, tris, view_proj(eyes), eyes.astype(np.float32), H, H, 1, 0.0,
+                 "lambert", color=white, target_pos=tpos, target_color=white)
+
+
 def sphere_tangents(pos: np.ndarray):
     """Raw per-vertex tangent (-sin phi, 0, cos phi), phi = atan2(z, x): the
     direction of growing u of the spherical UVs (orthogonalised per pixel)."""
