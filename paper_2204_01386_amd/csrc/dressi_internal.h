@@ -132,7 +132,7 @@ struct TriTiles {
 };
 size_t dressi_fragindex_bytes(int B, int K, int H, int W, int T);
 void dressi_fragindex_view(void *base, int B, int K, int H, int W, int T, FragLists &fl, TriTiles &tt);
-size_t dressi_fragindex_tmp_bytes(int B, int T);
+size_t dressi_fragindex_tmp_bytes(int B, int K, int H, int W, int T);
 void dressi_build_fragindex(const int32_t *tri_id, int B, int K, int H, int W, int T, void *base,
                             void *tmp, int32_t *zero_counts, hipStream_t s);
 

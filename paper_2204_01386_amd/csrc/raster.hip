@@ -1060,23 +1060,31 @@ __global__ void k_tt_fill(FragLists fl, int K, int T, int nt, const int32_t *__r
     }
 }
 
-__global__ void k_tt_sort(const int32_t *__restrict__ offsets, int2 *__restrict__ entries,
-                          int64_t n) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int a = offsets[i], e = offsets[i + 1];
-    for (int j = a + 1; j < e; j++) {
-        int2 v = entries[j];
-        int m = j - 1;
-        while (m >= a && entries[m].x > v.x) {
-            entries[m + 1] = entries[m];
-            m--;
-        }
-        entries[m + 1] = v;
+// One thread per entry: its place in its (view, triangle)'s list is the number
+// of that triangle's entries from lower tiles (a triangle has at most one
+// record per tile, so the tile indices in a list are distinct).  Writes the
+// lists in ascending tile order; the work per list grows with the square of
+// its length but runs one thread per entry.
+__global__ void k_tt_rank(FragLists fl, int K, int T, int nt, const int32_t *__restrict__ offsets,
+                          const int2 *__restrict__ unsorted, int2 *__restrict__ entries, int64_t nkeys) {
+    const int64_t total = offsets[nkeys];   // the number of entries (the scan's total)
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int2 ent = unsorted[e];
+        const int t = fl.rec_tri[(int64_t)ent.x * DRESSI_TILE_PIX * K + ent.y];
+        const int64_t key = (int64_t)(ent.x / nt) * T + t;
+        const int lo = offsets[key], hi = offsets[key + 1];
+        int rank = 0;
+        for (int j = lo; j < hi; j++) rank += unsorted[j].x < ent.x;
+        entries[lo + rank] = ent;
     }
 }
 
-size_t dressi_fragindex_tmp_bytes(int B, int T) { return dressi_scan_tmp_bytes((int64_t)B * T); }
+// scan temporary, then the unsorted triangle -> tiles entries
+size_t dressi_fragindex_tmp_bytes(int B, int K, int H, int W, int T) {
+    const int64_t n = (int64_t)B * tiles_x(W) * tiles_y(H) * DRESSI_TILE_PIX * K;
+    return (dressi_scan_tmp_bytes((int64_t)B * T) + 255) / 256 * 256 + sizeof(int2) * (size_t)n;
+}
 
 // counts: B*T zero counters (left at zero)
 void dressi_build_fragindex(const int32_t *tri_id, int B, int K, int H, int W, int T, void *base,
@@ -1090,9 +1098,14 @@ void dressi_build_fragindex(const int32_t *tri_id, int B, int K, int H, int W, i
                   fl.n_frag, fl.n_rec, fl.frag, fl.rec_tri, fl.rec_start, counts);
     int64_t n = (int64_t)B * T;
     dressi_exclusive_scan(counts, tt.offsets, n, tmp, s);
-    if (B * nt > 0)
-        DR_LAUNCH("k_tt_fill", (k_tt_fill), B * nt, 256, 0, s, fl, K, T, nt, tt.offsets, counts, tt.entries);
-    if (n > 0) DR_LAUNCH("k_tt_sort", (k_tt_sort), (int)((n + 255) / 256), 256, 0, s, tt.offsets, tt.entries, n);
+    int2 *unsorted = reinterpret_cast<int2 *>(static_cast<char *>(tmp) +
+                                              (dressi_scan_tmp_bytes(n) + 255) / 256 * 256);
+    const int64_t ne = (int64_t)B * nt * DRESSI_TILE_PIX * K;   // entry capacity (at least the entries)
+    if (B * nt > 0) {
+        DR_LAUNCH("k_tt_fill", (k_tt_fill), B * nt, 256, 0, s, fl, K, T, nt, tt.offsets, counts, unsorted);
+        DR_LAUNCH("k_tt_rank", (k_tt_rank), (int)std::min<int64_t>((ne + 255) / 256, 4096), 256, 0, s, fl, K, T,
+                  nt, tt.offsets, unsorted, tt.entries, n);
+    }
 }
 
 extern "C" size_t dressi_fragment_index_bytes(int B, int K, int H, int W, int T) {
@@ -1108,7 +1121,7 @@ extern "C" int dressi_fragment_index(dressi_ctx *ctx, const int32_t *tri_id, int
     if (!index || ((int64_t)B * H * W > 0 && !tri_id))
         return dressi_fail(ctx, DRESSI_EINVAL, "fragment_index: null pointer");
     hipStream_t st = (hipStream_t)stream;
-    int rc = dressi_scratch(ctx, dressi_fragindex_tmp_bytes(B, T), st);
+    int rc = dressi_scratch(ctx, dressi_fragindex_tmp_bytes(B, K, H, W, T), st);
     if (rc) return rc;
     rc = dressi_counters(ctx, (size_t)B * T, st);
     if (rc) return rc;
@@ -1358,7 +1371,7 @@ static int rasterize_bwd_impl(dressi_ctx *ctx, const float *pos_clip, const int3
     Carver c;
     size_t o_fi = frag_index ? 0 : c.take(dressi_fragindex_bytes(B, K, H, W, T));
     size_t o_adj = adj ? 0 : c.take(adjacency_buf_bytes(V, T));
-    size_t o_tmp = c.take(std::max(frag_index ? (size_t)0 : dressi_fragindex_tmp_bytes(B, T),
+    size_t o_tmp = c.take(std::max(frag_index ? (size_t)0 : dressi_fragindex_tmp_bytes(B, K, H, W, T),
                                    adj ? (size_t)0 : dressi_adjacency_tmp_bytes(V)));
     size_t o_part = c.take(sizeof(float) * partial_floats(B, K, H, W, 9));
     rc = dressi_scratch(ctx, c.off, st);
@@ -1439,7 +1452,7 @@ extern "C" size_t dressi_scratch_bytes(int B, int V, int T, int H, int W, int K,
         Carver c;
         c.take(dressi_fragindex_bytes(B, K, H, W, T));
         c.take(adjacency_buf_bytes(Vm, T));
-        c.take(std::max(dressi_fragindex_tmp_bytes(B, T), dressi_adjacency_tmp_bytes(Vm)));
+        c.take(std::max(dressi_fragindex_tmp_bytes(B, K, H, W, T), dressi_adjacency_tmp_bytes(Vm)));
         c.take(sizeof(float) * 3 * (size_t)(C > 9 ? C : 9) * B * T);
         c.take(sizeof(float) * partial_floats(B, K, H, W, 3 * (C > 3 ? C : 3)));
         upd(c.off);

@@ -66,3 +66,12 @@ def test_value_noise_range_and_tiling(H, W, C):
     assert t.shape == (H, W, C) and t.dtype == np.float32
     assert t.min() >= 0.0 and t.max() <= 1.0
     assert np.allclose(t.min(axis=(0, 1)), 0.0) and np.allclose(t.max(axis=(0, 1)), 1.0)
+
+
+def test_paper_table_scene_shapes():
+    """Sphere sizes near the paper's table meshes, six views, white Lambert."""
+    for T in (682, 14208, 51414):
+        sc = scenes.paper_table_scene(T, 256)
+        assert abs(sc.tris.shape[0] - T) / T < 0.02
+        assert sc.mvp.shape == (6, 4, 4) and sc.shading == "lambert" and sc.K == 1
+        assert np.all(sc.color == 1.0) and sc.tris.max() < sc.pos.shape[0]
