@@ -246,6 +246,28 @@ int dressi_texture_bwd(dressi_ctx *ctx, const float *tex, const dressi_tex_desc 
                        const float *coord, const int32_t *tri_id, int S, int H, int W,
                        const float *grad_out, float *grad_tex, float *grad_coord, void *stream);
 
+/* The two halves of the texture gradient of dressi_texture_bwd, for a scene
+ * whose geometry is held fixed while only textures are optimised (the
+ * paper's reactive cache, §3.2.3, skips the unchanged rasterization; its
+ * cross-platform table times texture-only iterations): the inverse-UV map
+ * depends only on coord and tri_id, so it is built once and every later
+ * step only gathers.
+ * dressi_invuv_bytes: size of the map, S * F * Ht * Wt int32 (F = 6 for a
+ * cube map, the layer count of an array, else 1); 0 for a bad descriptor.
+ * dressi_invuv_build: writes the map into caller-owned device memory `inv`
+ * (every cell -1, then the largest covered pixel index of each slice whose
+ * coordinate falls in it).  Texels are not read.
+ * dressi_texture_grad_invuv: grad_tex from grad_out [S,H,W,Ct] through a map
+ * built from the same coord and tri_id; bitwise what dressi_texture_bwd
+ * gives.  Both need tri_id, and Ht, Wt >= 3 for repeat wrap (DRESSI_EINVAL
+ * otherwise); inv is read, never written, by the gather. */
+size_t dressi_invuv_bytes(const dressi_tex_desc *td, int S);
+int dressi_invuv_build(dressi_ctx *ctx, const dressi_tex_desc *td, const float *coord,
+                       const int32_t *tri_id, int S, int H, int W, int32_t *inv, void *stream);
+int dressi_texture_grad_invuv(dressi_ctx *ctx, const dressi_tex_desc *td, const float *coord,
+                              const int32_t *tri_id, int S, int H, int W, const int32_t *inv,
+                              const float *grad_out, float *grad_tex, void *stream);
+
 /* ----------------------------------------------------------------------------
  * HardSoftRas blend (§3.4.3, BuildBlend):
  *   D_k = sigmoid(dist_k / sigma), w_k = D_k [tri_id_k >= 0],

@@ -68,6 +68,8 @@ _SIG = {
                                _vp, _vp, _vp, _vp, _vp],
     "dressi_texture": [_vp, _vp, C.POINTER(TexDesc), _vp, _vp, _i, _i, _i, _vp, _vp],
     "dressi_texture_bwd": [_vp, _vp, C.POINTER(TexDesc), _vp, _vp, _i, _i, _i, _vp, _vp, _vp, _vp],
+    "dressi_invuv_build": [_vp, C.POINTER(TexDesc), _vp, _vp, _i, _i, _i, _vp, _vp],
+    "dressi_texture_grad_invuv": [_vp, C.POINTER(TexDesc), _vp, _vp, _i, _i, _i, _vp, _vp, _vp, _vp],
     "dressi_softras": [_vp, _vp, _vp, _vp, _i, _i, _i, _i, _i, _f, _f, _i, _vp, _vp, _vp, _vp],
     "dressi_softras_bwd": [_vp, _vp, _vp, _vp, _i, _i, _i, _i, _i, _f, _vp, _vp, _vp, _vp, _vp, _vp],
     "dressi_transform": [_vp, _vp, _vp, _i, _i, _vp, _vp],
@@ -94,6 +96,8 @@ _lib.dressi_last_error.argtypes = [_vp]
 _lib.dressi_last_error.restype = C.c_char_p
 _lib.dressi_scratch_bytes.argtypes = [_i, _i, _i, _i, _i, _i, _f, _i, _i, _i64, _i]
 _lib.dressi_scratch_bytes.restype = C.c_size_t
+_lib.dressi_invuv_bytes.argtypes = [C.POINTER(TexDesc), _i]
+_lib.dressi_invuv_bytes.restype = C.c_size_t
 _lib.dressi_fragment_index_bytes.argtypes = [_i, _i, _i, _i, _i]
 _lib.dressi_fragment_index_bytes.restype = C.c_size_t
 _lib.dressi_profile_start.argtypes = [_i]
@@ -102,7 +106,7 @@ _lib.dressi_profile_read.argtypes = [C.POINTER(C.c_char_p), C.POINTER(C.c_float)
 _lib.dressi_profile_read.restype = C.c_int
 
 EXPORTED = sorted(list(_SIG) + ["dressi_last_error", "dressi_scratch_bytes", "dressi_fragment_index_bytes",
-                                "dressi_profile_start", "dressi_profile_read"])
+                                "dressi_invuv_bytes", "dressi_profile_start", "dressi_profile_read"])
 
 
 class DressiError(RuntimeError):
@@ -306,6 +310,42 @@ def dressi_texture_bwd(tex, coord, tri_id, grad_out, kind=TEX_2D, wrap_u=WRAP_RE
                                       S, H, W, _ptr(grad_out), _ptr(gt), _ptr(gc), _stream()),
               "dressi_texture_bwd")
     return gt, gc
+
+
+def dressi_invuv_build(tex, coord, tri_id, kind=TEX_2D, wrap_u=WRAP_REPEAT, wrap_v=WRAP_CLAMP, tri_layer=None):
+    """The inverse-UV map [S,F,Ht,Wt] int32 of coord/tri_id for a texture shaped like `tex`."""
+    _need(coord, torch.float32, "coord")
+    if tri_id is not None:
+        _need(tri_id, torch.int32, "tri_id")
+    d = _desc(tex, kind, wrap_u, wrap_v, tri_layer)
+    lead = coord.shape[:-1]
+    H, W = lead[-2], lead[-1]
+    S = coord.numel() // (coord.shape[-1] * H * W)
+    n = int(_lib.dressi_invuv_bytes(C.byref(d), S)) // 4
+    inv = torch.empty(n, dtype=torch.int32, device=coord.device)
+    ctx = context(coord.device.index)
+    ctx.check(_lib.dressi_invuv_build(ctx.handle, C.byref(d), _ptr(coord), _ptr(tri_id), S, H, W, _ptr(inv),
+                                      _stream()), "dressi_invuv_build")
+    return inv
+
+
+def dressi_texture_grad_invuv(tex, coord, tri_id, inv, grad_out, kind=TEX_2D, wrap_u=WRAP_REPEAT,
+                              wrap_v=WRAP_CLAMP, tri_layer=None):
+    """Texture gradient gathered through a map from dressi_invuv_build."""
+    _need(grad_out, torch.float32, "grad_out")
+    _need(inv, torch.int32, "inv")
+    d = _desc(tex, kind, wrap_u, wrap_v, tri_layer)
+    lead = coord.shape[:-1]
+    H, W = lead[-2], lead[-1]
+    S = coord.numel() // (coord.shape[-1] * H * W)
+    if inv.numel() * 4 != int(_lib.dressi_invuv_bytes(C.byref(d), S)):
+        raise ValueError("inverse-UV map of the wrong size for this texture and coordinate set")
+    gt = torch.empty_like(tex)
+    ctx = context(coord.device.index)
+    ctx.check(_lib.dressi_texture_grad_invuv(ctx.handle, C.byref(d), _ptr(coord), _ptr(tri_id), S, H, W,
+                                             _ptr(inv), _ptr(grad_out), _ptr(gt), _stream()),
+              "dressi_texture_grad_invuv")
+    return gt
 
 
 def dressi_softras(color, dist, tri_id, sigma, delta, mode=BLEND_HSR):

@@ -499,6 +499,57 @@ extern "C" int dressi_texture(dressi_ctx *ctx, const float *tex, const dressi_te
     return dressi_launch_check(ctx, "texture");
 }
 
+// Records every covered pixel of the S slices in its cell of the inverse-UV
+// map (cleared to -1 first) and, when grad_coord is given, writes d out / d coord.
+static void tex_bwd_pixels(const float *tex, const dressi_tex_desc &td, const float *coord,
+                           const int32_t *tri_id, int64_t npix, int S, const float *grad_out,
+                           float *grad_coord, int32_t *inv, hipStream_t st) {
+    const int64_t n = (int64_t)S * npix;
+    // cleared for every slice, also when slices are empty: the gather reads them all
+    if (inv && S > 0) dressi_fill_i32(inv, -1, (int64_t)tex_faces(td) * td.Ht * td.Wt * S, st);
+    if (n == 0 || (!grad_coord && !inv)) return;
+    const int g = (int)((n + 255) / 256);
+    switch (grad_coord && aligned16(tex, grad_out) ? td.Ct : 0) {
+    case 3: DR_LAUNCH("k_tex_bwd_pixel", (k_tex_bwd_pixel<3>), g, 256, 0, st, tex, td, coord, tri_id, npix, S,
+                      grad_out, grad_coord, inv); break;
+    case 4: DR_LAUNCH("k_tex_bwd_pixel", (k_tex_bwd_pixel<4>), g, 256, 0, st, tex, td, coord, tri_id, npix, S,
+                      grad_out, grad_coord, inv); break;
+    case 8: DR_LAUNCH("k_tex_bwd_pixel", (k_tex_bwd_pixel<8>), g, 256, 0, st, tex, td, coord, tri_id, npix, S,
+                      grad_out, grad_coord, inv); break;
+    default: DR_LAUNCH("k_tex_bwd_pixel", (k_tex_bwd_pixel<0>), g, 256, 0, st, tex, td, coord, tri_id, npix,
+                       S, grad_out, grad_coord, inv); break;
+    }
+}
+
+// The texture gradient gathered from a built inverse-UV map.  Small textures
+// (an environment map) have few texel blocks: their slices are split over the
+// grid as well and the parts summed afterwards in `part`.
+static void tex_gather(const dressi_tex_desc &td, const float *coord, const int32_t *tri_id, int64_t npix,
+                       int S, const int32_t *inv, const float *grad_out, float *part, float *grad_tex,
+                       hipStream_t st) {
+    const int64_t cells = (int64_t)tex_faces(td) * td.Ht * td.Wt;
+    const int nsplit = dressi_invuv_nsplit(cells, S);
+    float *dst = nsplit > 1 ? part : grad_tex;
+    const int ty = IvGeom<DRESSI_IV_SG>::TY;
+    dim3 g((unsigned)((td.Wt + IV_T - 1) / IV_T), (unsigned)((td.Ht + ty - 1) / ty),
+           (unsigned)(tex_faces(td) * nsplit));
+    const int ct = aligned16(grad_out, dst) ? td.Ct : 0;
+    launch_gather<DRESSI_IV_SG>(ct, g, st, td, coord, tri_id, npix, S, nsplit, inv, grad_out, dst);
+    if (nsplit > 1) {
+        int64_t ne = cells * td.Ct;
+        DR_LAUNCH("k_invuv_reduce", (k_invuv_reduce), (int)((ne + 255) / 256), 256, 0, st, part, nsplit, ne,
+                  grad_tex);
+    }
+}
+
+static int check_grad_tex(dressi_ctx *ctx, const dressi_tex_desc *td, const int32_t *tri_id, const char *what) {
+    if (!tri_id) return dressi_fail(ctx, DRESSI_EINVAL, what);
+    if (td->kind != DRESSI_TEX_CUBE &&
+        ((td->wrap_u == DRESSI_WRAP_REPEAT && td->Wt < 3) || (td->wrap_v == DRESSI_WRAP_REPEAT && td->Ht < 3)))
+        return dressi_fail(ctx, DRESSI_EINVAL, "texture_bwd: repeat wrap needs at least 3 texels");
+    return DRESSI_OK;
+}
+
 extern "C" int dressi_texture_bwd(dressi_ctx *ctx, const float *tex, const dressi_tex_desc *td,
                                   const float *coord, const int32_t *tri_id, int S, int H, int W,
                                   const float *grad_out, float *grad_tex, float *grad_coord,
@@ -507,11 +558,8 @@ extern "C" int dressi_texture_bwd(dressi_ctx *ctx, const float *tex, const dress
     if (rc) return rc;
     int64_t npix = (int64_t)H * W, n = (int64_t)S * npix;
     if (n > 0 && !grad_out) return dressi_fail(ctx, DRESSI_EINVAL, "texture_bwd: null grad_out");
-    if (grad_tex && !tri_id)
-        return dressi_fail(ctx, DRESSI_EINVAL, "texture_bwd: the texture gradient needs tri_id");
-    if (grad_tex && td->kind != DRESSI_TEX_CUBE &&
-        ((td->wrap_u == DRESSI_WRAP_REPEAT && td->Wt < 3) || (td->wrap_v == DRESSI_WRAP_REPEAT && td->Ht < 3)))
-        return dressi_fail(ctx, DRESSI_EINVAL, "texture_bwd: repeat wrap needs at least 3 texels");
+    if (grad_tex && (rc = check_grad_tex(ctx, td, tri_id, "texture_bwd: the texture gradient needs tri_id")))
+        return rc;
     hipStream_t st = (hipStream_t)stream;
     int32_t *inv = nullptr;
     float *part = nullptr;
@@ -524,39 +572,46 @@ extern "C" int dressi_texture_bwd(dressi_ctx *ctx, const float *tex, const dress
         if (rc) return rc;
         inv = at<int32_t>(ctx->scratch, o_inv);
         part = at<float>(ctx->scratch, o_part);
-        if (n > 0) dressi_fill_i32(inv, -1, cells * S, st);
     }
-    if (n > 0 && (grad_coord || inv))
-    {
-        const int g = (int)((n + 255) / 256);
-        switch (aligned16(tex, grad_out) ? td->Ct : 0) {
-        case 3: DR_LAUNCH("k_tex_bwd_pixel", (k_tex_bwd_pixel<3>), g, 256, 0, st, tex, *td, coord, tri_id, npix, S,
-                          grad_out, grad_coord, inv); break;
-        case 4: DR_LAUNCH("k_tex_bwd_pixel", (k_tex_bwd_pixel<4>), g, 256, 0, st, tex, *td, coord, tri_id, npix, S,
-                          grad_out, grad_coord, inv); break;
-        case 8: DR_LAUNCH("k_tex_bwd_pixel", (k_tex_bwd_pixel<8>), g, 256, 0, st, tex, *td, coord, tri_id, npix, S,
-                          grad_out, grad_coord, inv); break;
-        default: DR_LAUNCH("k_tex_bwd_pixel", (k_tex_bwd_pixel<0>), g, 256, 0, st, tex, *td, coord, tri_id, npix,
-                           S, grad_out, grad_coord, inv); break;
-        }
-    }
-    if (grad_tex) {
-        // Small textures (an environment map) have few texel blocks: split the
-        // slices over the grid as well and sum the parts afterwards.
-        int nsplit = 1;
-        nsplit = dressi_invuv_nsplit(cells, S);
-        float *dst = grad_tex;
-        if (nsplit > 1) dst = part;
-        const int ty = IvGeom<DRESSI_IV_SG>::TY;
-        dim3 g((unsigned)((td->Wt + IV_T - 1) / IV_T), (unsigned)((td->Ht + ty - 1) / ty),
-               (unsigned)(tex_faces(*td) * nsplit));
-        const int ct = aligned16(grad_out, dst) ? td->Ct : 0;
-        launch_gather<DRESSI_IV_SG>(ct, g, st, *td, coord, tri_id, npix, S, nsplit, inv, grad_out, dst);
-        if (nsplit > 1) {
-            int64_t ne = cells * td->Ct;
-            DR_LAUNCH("k_invuv_reduce", (k_invuv_reduce), (int)((ne + 255) / 256), 256, 0, st, part, nsplit, ne,
-                      grad_tex);
-        }
-    }
+    tex_bwd_pixels(tex, *td, coord, tri_id, npix, S, grad_out, grad_coord, inv, st);
+    if (grad_tex) tex_gather(*td, coord, tri_id, npix, S, inv, grad_out, part, grad_tex, st);
     return dressi_launch_check(ctx, "texture_bwd");
+}
+
+extern "C" size_t dressi_invuv_bytes(const dressi_tex_desc *td, int S) {
+    if (!td || S < 0 || td->Ht < 1 || td->Wt < 1) return 0;
+    if (td->kind == DRESSI_TEX_2D_ARRAY && td->layers < 1) return 0;
+    return sizeof(int32_t) * (size_t)tex_faces(*td) * td->Ht * td->Wt * (size_t)S;
+}
+
+extern "C" int dressi_invuv_build(dressi_ctx *ctx, const dressi_tex_desc *td, const float *coord,
+                                  const int32_t *tri_id, int S, int H, int W, int32_t *inv, void *stream) {
+    // the texels themselves are not read: any non-null pointer passes the shared check
+    int rc = check_tex(ctx, coord, td, coord, tri_id, S, H, W);
+    if (rc) return rc;
+    if ((rc = check_grad_tex(ctx, td, tri_id, "invuv_build: needs tri_id"))) return rc;
+    if (S > 0 && !inv) return dressi_fail(ctx, DRESSI_EINVAL, "invuv_build: null inv");
+    tex_bwd_pixels(nullptr, *td, coord, tri_id, (int64_t)H * W, S, nullptr, nullptr, inv, (hipStream_t)stream);
+    return dressi_launch_check(ctx, "invuv_build");
+}
+
+extern "C" int dressi_texture_grad_invuv(dressi_ctx *ctx, const dressi_tex_desc *td, const float *coord,
+                                         const int32_t *tri_id, int S, int H, int W, const int32_t *inv,
+                                         const float *grad_out, float *grad_tex, void *stream) {
+    int rc = check_tex(ctx, coord, td, coord, tri_id, S, H, W);
+    if (rc) return rc;
+    if ((rc = check_grad_tex(ctx, td, tri_id, "texture_grad_invuv: needs tri_id"))) return rc;
+    if (!grad_tex) return dressi_fail(ctx, DRESSI_EINVAL, "texture_grad_invuv: null grad_tex");
+    if (S > 0 && (!inv || (H * W > 0 && !grad_out)))
+        return dressi_fail(ctx, DRESSI_EINVAL, "texture_grad_invuv: null inv or grad_out");
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t cells = (int64_t)tex_faces(*td) * td->Ht * td->Wt;
+    float *part = nullptr;
+    const size_t pb = dressi_invuv_part_bytes(cells, td->Ct, S);
+    if (pb) {
+        if ((rc = dressi_scratch(ctx, pb, st))) return rc;
+        part = at<float>(ctx->scratch, 0);
+    }
+    tex_gather(*td, coord, tri_id, (int64_t)H * W, S, inv, grad_out, part, grad_tex, st);
+    return dressi_launch_check(ctx, "texture_grad_invuv");
 }

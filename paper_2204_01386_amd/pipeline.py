@@ -378,6 +378,98 @@ class Step(_TwoStreams):
         return out
 
 
+class TextureStep:
+    """Texture-only optimisation of a scene whose geometry is held fixed.
+
+    The paper's reactive cache (§3.2.3) skips graph nodes whose inputs did
+    not change since they were last computed; for texture optimisation that
+    removes the whole rasterization (its cross-platform table times
+    texture-only and geometry iterations separately).  Here the cached nodes
+    are explicit: the fragments (tri_id, barycentrics, soft distances), the
+    interpolated attributes and texture coordinates, and the albedo texture's
+    inverse-UV map are computed once from the wrapped Step's geometry.  A step
+    then runs only what depends on the textures: sampling, shading, the blend,
+    the loss, their adjoints and the texel gather from the cached map.  An
+    environment map looked up along a normal-mapped reflection stays fully
+    per step (its lookup direction moves with the normal map).  Images, loss
+    and texture gradients are bitwise those of the full step with the same
+    parameters; refresh() recomputes the cache after the geometry changed."""
+
+    def __init__(self, step: Step):
+        if step.tex is None:
+            raise ValueError("a texture-only step needs a textured scene")
+        self.st = step
+        S = step.B * step.K
+        n = int(_lib.dressi_invuv_bytes(C.byref(step.desc), S)) // 4
+        self.inv = torch.empty(n, dtype=torch.int32, device=step.dev)
+        self.refresh()
+
+    def refresh(self):
+        """Recomputes the cached geometry-only nodes (after the positions,
+        cameras or mesh changed)."""
+        st = self.st
+        st.forward()
+        st._chk(_lib.dressi_invuv_build(st.ctx.handle, C.byref(st.desc), _p(st.uvbuf), _p(st.tri_id), st.B * st.K,
+                                        st.H, st.W, _p(self.inv), st._s()), "invuv_build")
+
+    def forward(self):
+        st = self.st
+        h, s, ck = st.ctx.handle, st._s(), st._chk
+        B, K, H, W = st.B, st.K, st.H, st.W
+        ck(_lib.dressi_texture(h, _p(st.tex), C.byref(st.desc), _p(st.uvbuf), _p(st.tri_id), B * K, H, W,
+                               _p(st.samp), s), "texture")
+        if st.env is not None:
+            ck(_lib.dressi_shade(h, st.mode, C.byref(st._fin_dir), _p(st.eye), _p(st.tri_id), B, K * H * W,
+                                 None, _p(st.dir), s), "shade dir")
+            ck(_lib.dressi_texture(h, _p(st.env), C.byref(st.env_desc), _p(st.dir), _p(st.tri_id), B * K, H, W,
+                                   _p(st.env_s), s), "texture env")
+        ck(_lib.dressi_shade(h, st.mode, C.byref(st._fin), _p(st.eye), _p(st.tri_id), B, K * H * W,
+                             _p(st.layer_color), None, s), "shade")
+        ck(_lib.dressi_softras(h, _p(st.layer_color), _p(st.dist), _p(st.tri_id), B, K, H, W, 3, st.sigma,
+                               st.delta, st.blend, _p(st.color), _p(st.sil), _p(st.E), s), "softras")
+
+    def loss_and_grad(self):
+        self.st.loss_and_grad()
+
+    def backward(self):
+        st = self.st
+        h, s, ck = st.ctx.handle, st._s(), st._chk
+        B, K, H, W = st.B, st.K, st.H, st.W
+        Npv = K * H * W
+        ck(_lib.dressi_softras_bwd(h, _p(st.layer_color), _p(st.dist), _p(st.tri_id), B, K, H, W, 3, st.sigma,
+                                   _p(st.E), _p(st.g_color), _p(st.g_sil), _p(st.g_layer), None, s),
+           "softras_bwd")
+        if st.env is not None:
+            ge = Bd.FragGrad()
+            ge.env, ge.env_stride = _cp(st.g_env_s, 0), 3
+            ck(_lib.dressi_shade_bwd(h, st.mode, C.byref(st._fin), _p(st.eye), _p(st.tri_id), B, Npv,
+                                     _p(st.g_layer), None, C.byref(ge), s), "shade_bwd env")
+            st._texture_bwd(st.env, st.env_desc, st.dir, B * K, st.g_env_s, st.g_envtex, st.g_dir,
+                            "texture_bwd env")
+        g = Bd.FragGrad()
+        g.albedo, g.albedo_stride = _cp(st.g_samp, 0), st.Ct
+        if st.mode == Bd.SHADE_PHONG_ENV:
+            g.nmap, g.nmap_stride = _cp(st.g_samp, 4), st.Ct
+        ck(_lib.dressi_shade_bwd(h, st.mode, C.byref(st._fin), _p(st.eye), _p(st.tri_id), B, Npv, _p(st.g_layer),
+                                 _p(st.g_dir), C.byref(g), s), "shade_bwd")
+        ck(_lib.dressi_texture_grad_invuv(h, C.byref(st.desc), _p(st.uvbuf), _p(st.tri_id), B * K, H, W,
+                                          _p(self.inv), _p(st.g_samp), _p(st.g_tex), s), "texture_grad_invuv")
+        st._join()
+
+    def run(self):
+        """One texture-only step: forward, loss and gradient, backward."""
+        self.forward()
+        self.loss_and_grad()
+        self.backward()
+
+    def grads(self):
+        """Gradients of the loss w.r.t. the textures."""
+        out = {"tex": self.st.grads()["tex"]}
+        if self.st.g_envtex is not None:
+            out["env"] = self.st.g_envtex
+        return out
+
+
 def make_target(scene: Scene, device="cuda", views=None) -> Step:
     """Renders the scene's target (perturbed mesh / target texture) once."""
     f32 = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(device)
