@@ -59,6 +59,8 @@ def parse():
     ap.add_argument("--no-uneven", dest="uneven", action="store_false",
                     help="skip the 64-instance uneven batch measurement")
     ap.add_argument("--uneven-steps", type=int, default=20)
+    ap.add_argument("--no-fit", dest="fit", action="store_false",
+                    help="skip the two-stage fit (sphere to pear, positions then texture)")
     ap.add_argument("--copy-ref", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of MIB MiB (reference for HBM counters)")
     ap.add_argument("--paper-table", action="store_true",
@@ -582,6 +584,23 @@ def main():
     # ---- the uneven 64-instance batch beside its per-instance form ---------
     uneven = uneven_line(args.uneven_steps, max(1, args.profile_steps // 4)) if args.uneven and args.config == 2 else None
 
+    # ---- the two-stage fit of the cross-platform application ---------------
+    fit = None
+    if args.fit and args.config == 2:
+        from paper_2204_01386_amd import scenes as _sc
+        from paper_2204_01386_amd.fit import run_fit
+        fr = run_fit(_sc.fit_scene())
+        c = fr["curve"]
+        first = next(x for x in c if x["stage"] == "silhouette")
+        last_sil = [x for x in c if x["stage"] == "silhouette"][-1]
+        t0 = next(x for x in c if x["stage"] == "texture")
+        last = c[-1]
+        fit = {"workload": fr["workload"], "views": fr["views"], "H": fr["H"], "triangles": fr["triangles"],
+               "iterations": fr["iterations"], "ms_per_iteration": fr["ms_per_iteration"],
+               "silhouette_l2": [first["sil_l2"], last_sil["sil_l2"]],
+               "surface_distance": [first["surface_distance"], last_sil["surface_distance"]],
+               "color_l2": [t0["color_l2"], last["color_l2"]], "bin_overflow": fr["bin_overflow"]}
+
     # ---- CPU baseline: the oracle's step on the same workload --------------
     cpu = None
     if not args.no_cpu:
@@ -637,6 +656,7 @@ def main():
                      "ms_per_launch": round(dom[2], 5)},
         "cpu_baseline": cpu,
         "paper_context": PAPER_CONTEXT,
+        "fit": fit,
         "multiview": multi,
         "uneven": uneven,
         "kernels": kernel_rows,

@@ -388,6 +388,38 @@ int dressi_loss_l2(dressi_ctx *ctx, const float *color, const float *sil, const 
                    const float *weight, int B, int H, int W, float *loss, float *grad_color,
                    float *grad_sil, void *stream);
 
+/* ----------------------------------------------------------------------------
+ * The optimisation loop around the step (§4.1: vertex positions fitted to
+ * silhouettes under a scheduled Laplacian regulariser, then the albedo
+ * texture to colours, both with Adam).
+ * ------------------------------------------------------------------------- */
+
+/* One Adam step (Kingma & Ba, Algorithm 1) on n floats, in place:
+ *   m = b1 m + (1-b1) g,  v = b2 v + (1-b2) g^2,
+ *   param -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps),
+ * with t the 1-based number of this step.  `state` is caller-owned device
+ * memory of DRESSI_ADAM_STATE_BYTES, 16-byte aligned and zeroed before the
+ * first step (one per parameter tensor); the call advances its step count
+ * on the stream, so a captured step replays successive Adam steps.  m and v
+ * (n floats each) start at zero.  betas in [0, 1), eps > 0, else EINVAL. */
+#define DRESSI_ADAM_STATE_BYTES 16
+int dressi_adam(dressi_ctx *ctx, float *param, const float *grad, float *m, float *v, int64_t n,
+                float lr, float beta1, float beta2, float eps, void *state, void *stream);
+
+/* Laplacian regulariser on vertex positions pos [V,3] of tris [T,3]:
+ *   delta_v = p_v - (sum over the triangles t of v's fan of t's two other
+ *             corners) / (2 |fan(v)|)   (0 for a vertex in no triangle),
+ * the uniform (umbrella) Laplacian on closed manifold meshes;
+ *   R = lam / V * sum_v |delta_v|^2,  lam = lam0 * gamma^i,
+ * i = the step count in adam_state (the positions' Adam state; NULL: i = 0),
+ * read before that step's dressi_adam.  Writes, when non-NULL,
+ * grad_out [V,3] = grad_in (NULL = 0) + dR/dpos (grad_out may be grad_in)
+ * and value [1] (device) = R.  adj: the mesh adjacency (dressi_adjacency) or
+ * NULL to build it internally.  Sums in double, fixed order. */
+int dressi_laplacian_reg(dressi_ctx *ctx, const float *pos, const int32_t *tris, int V, int T,
+                         const int32_t *adj, float lam0, float gamma, const void *adam_state,
+                         const float *grad_in, float *grad_out, float *value, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -68,6 +68,8 @@ _SIG = {
                                _vp, _vp, _vp, _vp, _vp],
     "dressi_texture": [_vp, _vp, C.POINTER(TexDesc), _vp, _vp, _i, _i, _i, _vp, _vp],
     "dressi_texture_bwd": [_vp, _vp, C.POINTER(TexDesc), _vp, _vp, _i, _i, _i, _vp, _vp, _vp, _vp],
+    "dressi_adam": [_vp, _vp, _vp, _vp, _vp, _i64, _f, _f, _f, _f, _vp, _vp],
+    "dressi_laplacian_reg": [_vp, _vp, _vp, _i, _i, _vp, _f, _f, _vp, _vp, _vp, _vp, _vp],
     "dressi_invuv_build": [_vp, C.POINTER(TexDesc), _vp, _vp, _i, _i, _i, _vp, _vp],
     "dressi_texture_grad_invuv": [_vp, C.POINTER(TexDesc), _vp, _vp, _i, _i, _i, _vp, _vp, _vp, _vp],
     "dressi_softras": [_vp, _vp, _vp, _vp, _i, _i, _i, _i, _i, _f, _f, _i, _vp, _vp, _vp, _vp],
@@ -346,6 +348,41 @@ def dressi_texture_grad_invuv(tex, coord, tri_id, inv, grad_out, kind=TEX_2D, wr
                                              _ptr(inv), _ptr(grad_out), _ptr(gt), _stream()),
               "dressi_texture_grad_invuv")
     return gt
+
+
+ADAM_STATE_BYTES = 16
+
+
+def adam_state(device=None):
+    """A zeroed Adam step state (DRESSI_ADAM_STATE_BYTES on the device)."""
+    return torch.zeros(ADAM_STATE_BYTES // 4, dtype=torch.int32, device=device or "cuda")
+
+
+def dressi_adam(param, grad, m, v, state, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One in-place Adam step on param, m, v (all float32, same size)."""
+    for t, nm in ((param, "param"), (grad, "grad"), (m, "m"), (v, "v")):
+        _need(t, torch.float32, nm)
+    _need(state, torch.int32, "state")
+    n = param.numel()
+    if grad.numel() != n or m.numel() != n or v.numel() != n or state.numel() * 4 != ADAM_STATE_BYTES:
+        raise DressiError("dressi_adam: size mismatch")
+    ctx = context(param.device.index)
+    ctx.check(_lib.dressi_adam(ctx.handle, _ptr(param), _ptr(grad), _ptr(m), _ptr(v), n, lr, beta1, beta2, eps,
+                               _ptr(state), _stream()), "dressi_adam")
+
+
+def dressi_laplacian_reg(pos, tris, lam0, gamma=1.0, state=None, grad_in=None, adj=None, need_grad=True):
+    """(grad_out [V,3] or None, value [1]) of the Laplacian regulariser."""
+    _need(pos, torch.float32, "pos")
+    _need(tris, torch.int32, "tris")
+    V, T = pos.shape[0], tris.shape[0]
+    g = torch.empty_like(pos) if need_grad else None
+    val = torch.empty(1, dtype=torch.float32, device=pos.device)
+    ctx = context(pos.device.index)
+    ctx.check(_lib.dressi_laplacian_reg(ctx.handle, _ptr(pos), _ptr(tris), V, T, _ptr(adj), lam0, gamma,
+                                        _ptr(state), _ptr(grad_in), _ptr(g), _ptr(val), _stream()),
+              "dressi_laplacian_reg")
+    return g, val
 
 
 def dressi_softras(color, dist, tri_id, sigma, delta, mode=BLEND_HSR):

@@ -1214,23 +1214,38 @@ __device__ __forceinline__ void rast_frag_grad(const TriSetup &s, int x, int y, 
         const int Ya = ne == 0 ? s.Y[1] : (ne == 1 ? s.Y[2] : s.Y[0]);
         const int Xc = ne == 0 ? s.X[2] : (ne == 1 ? s.X[0] : s.X[1]);
         const int Yc = ne == 0 ? s.Y[2] : (ne == 1 ? s.Y[0] : s.Y[1]);
-        float sxa = (float)Xa * (1.0f / 256.0f), sya = (float)Ya * (1.0f / 256.0f);
-        float sxc = (float)Xc * (1.0f / 256.0f), syc = (float)Yc * (1.0f / 256.0f);
-        float Px = (float)x + 0.5f, Py = (float)y + 0.5f;
-        float ex = sxc - sxa, ey = syc - sya;
-        float tt = ((Px - sxa) * ex + (Py - sya) * ey) / (ex * ex + ey * ey);
-        tt = fminf(fmaxf(tt, 0.0f), 1.0f);
-        float cx = sxa + tt * ex, cy = sya + tt * ey;
-        float dx = Px - cx, dy = Py - cy;
-        float d = sqrtf(dx * dx + dy * dy);
-        if (d > 0.0f) {
-            float sg = (in ? gdist : -gdist) / ((float)W * d);
-            float ga = sg * (1.0f - tt), gc = sg * tt;
+        // The vector from the closest point of the segment to the pixel, from
+        // exact fixed-point quantities (a difference of nearby float screen
+        // coordinates would lose it near the edge, where the weights are
+        // largest): q = p - a, e = c - a; inside the segment it is the part of
+        // q perpendicular to e, (E / |e|^2) (-e_y, e_x) with E = e x q the
+        // exact edge function; past an end it is p minus that end.
+        const double ex = (double)(Xc - Xa), ey = (double)(Yc - Ya);
+        const double qx = (double)(px - Xa), qy = (double)(py - Ya);
+        const double len2 = ex * ex + ey * ey;
+        double tt = (qx * ex + qy * ey) / len2, dx, dy;
+        if (tt <= 0.0) {
+            tt = 0.0;
+            dx = qx;
+            dy = qy;
+        } else if (tt >= 1.0) {
+            tt = 1.0;
+            dx = (double)(px - Xc);
+            dy = (double)(py - Yc);
+        } else {
+            const double En = ne == 0 ? E[0] : (ne == 1 ? E[1] : E[2]);
+            dx = -En * ey / len2;
+            dy = En * ex / len2;
+        }
+        const double d = sqrt(dx * dx + dy * dy);   // fixed-point units: the ratio dx / d is what matters
+        if (d > 0.0) {
+            const double sg = (double)(in ? gdist : -gdist) / ((double)W * d);
+            const double ga = sg * (1.0 - tt), gc = sg * tt;
 #pragma unroll
             for (int i = 0; i < 3; i++) {
                 const bool is_a = i == (ne + 1) % 3, is_c = i == (ne + 2) % 3;
-                gsx[i] -= is_a ? ga * dx : (is_c ? gc * dx : 0.0f);
-                gsy[i] -= is_a ? ga * dy : (is_c ? gc * dy : 0.0f);
+                gsx[i] -= (float)(is_a ? ga * dx : (is_c ? gc * dx : 0.0));
+                gsy[i] -= (float)(is_a ? ga * dy : (is_c ? gc * dy : 0.0));
             }
         }
     }

@@ -45,7 +45,20 @@ __global__ void k_dilate_rows(const uint8_t *__restrict__ bnd, int B, int H, int
     rows[gid] = v;
 }
 
-__device__ __forceinline__ float sigmoidf_(float x) { return 1.0f / (1.0f + expf(-x)); }
+// sigmoid(x) and 1 - sigmoid(x) = sigmoid(-x), each to full relative
+// precision: the complement is never formed by subtracting from 1, which
+// would lose it where the sigmoid is near 1 (its derivative w (1 - w) and
+// the silhouette's product of complements use it).
+__device__ __forceinline__ float sigmoid_pair(float x, float &q) {
+    if (x >= 0.0f) {
+        const float e = expf(-x), w = 1.0f / (1.0f + e);
+        q = e * w;
+        return w;
+    }
+    const float e = expf(x);
+    q = 1.0f / (1.0f + e);
+    return e * q;
+}
 
 template <int K>
 __global__ void k_blend(const float *__restrict__ color, const float *__restrict__ dist,
@@ -87,10 +100,11 @@ __global__ void k_blend(const float *__restrict__ color, const float *__restrict
         w[k] = 0.0f;
         if (tri_id[o] < 0) continue;
         float d = dist ? dist[o] : 0.0f;
-        w[k] = sigmoidf_(d * inv_sigma);
+        float q;
+        w[k] = sigmoid_pair(d * inv_sigma, q);
         nS++;
         Wsum += w[k];
-        prod *= (1.0f - w[k]);
+        prod *= q;
     }
     float inv = nS > 0 ? 1.0f / Wsum : 0.0f;
     for (int c = 0; c < Cc; c++) {
@@ -128,14 +142,15 @@ __global__ void k_blend_bwd(const float *__restrict__ color, const float *__rest
         }
         return;
     }
-    float w[K];
+    float w[K], q[K];   // w_k and its complement 1 - w_k
     bool S[K];
     float Wsum = 0.0f;
 #pragma unroll
     for (int k = 0; k < K; k++) {
         int64_t o = o1 + (int64_t)k * N;
         S[k] = tri_id[o] >= 0;
-        w[k] = S[k] ? sigmoidf_((dist ? dist[o] : 0.0f) * inv_sigma) : 0.0f;
+        q[k] = 1.0f;
+        w[k] = S[k] ? sigmoid_pair((dist ? dist[o] : 0.0f) * inv_sigma, q[k]) : 0.0f;
         Wsum += w[k];
     }
     float inv = Wsum > 0.0f ? 1.0f / Wsum : 0.0f;
@@ -146,7 +161,7 @@ __global__ void k_blend_bwd(const float *__restrict__ color, const float *__rest
         float others = 1.0f;
 #pragma unroll
         for (int j = 0; j < K; j++)
-            if (j != k && S[j]) others *= (1.0f - w[j]);
+            if (j != k && S[j]) others *= q[j];
         gw[k] = gs * others;
     }
     for (int c = 0; c < Cc; c++) {
@@ -170,7 +185,7 @@ __global__ void k_blend_bwd(const float *__restrict__ color, const float *__rest
 #pragma unroll
         for (int k = 0; k < K; k++) {
             int64_t o = o1 + (int64_t)k * N;
-            grad_dist[o] = S[k] ? gw[k] * w[k] * (1.0f - w[k]) * inv_sigma : 0.0f;
+            grad_dist[o] = S[k] ? gw[k] * w[k] * q[k] * inv_sigma : 0.0f;
         }
     }
 }

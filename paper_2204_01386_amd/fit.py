@@ -1,0 +1,117 @@
+"""The two-stage fit of the paper's cross-platform application (§4.1) run to
+convergence on the GPU: vertex positions from silhouettes under the
+scheduled Laplacian regulariser, then the albedo texture on the fitted
+geometry.  Both stages run as captured graphs replayed once per iteration.
+Reports the convergence curve (silhouette and colour L2, and the mean
+distance of the fitted vertices to the target surface) and the time of one
+iteration of each stage."""
+from __future__ import annotations
+
+import numpy as np
+import torch
+from scipy.spatial import cKDTree
+
+from .pipeline import FitLoop, Step, make_target
+from .scenes import Scene
+
+
+def surface_samples(pos: np.ndarray, tris: np.ndarray, n: int = 6) -> np.ndarray:
+    """Points on every triangle at the barycentric grid of step 1/n (interior
+    and edges)."""
+    ij = [(i, j) for i in range(n + 1) for j in range(n + 1 - i)]
+    w = np.array([(i / n, j / n, 1.0 - (i + j) / n) for i, j in ij])
+    p = pos[tris].astype(np.float64)                       # [T,3,3]
+    return np.einsum("kc,tcd->tkd", w, p).reshape(-1, 3)
+
+
+def mean_surface_distance(pos: np.ndarray, tree: cKDTree) -> float:
+    d, _ = tree.query(pos.astype(np.float64))
+    return float(d.mean())
+
+
+def _sil_l2(st) -> float:
+    return float(((st.sil - st.target[..., 3]) ** 2).mean().item())
+
+
+def _col_l2(st) -> float:
+    m = st.target[..., 3:4] > 0
+    return float((((st.color - st.target[..., :3]) ** 2) * m).sum().item() / max(1, int(m.sum().item())))
+
+
+def _capture(fn):
+    fn()                      # eager: sizes the scratch, takes the first iteration
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        fn()
+    return g
+
+
+def _time(g, n: int) -> float:
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(n):
+        g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / n
+
+
+def run_fit(scene: Scene, n_sil: int = 300, n_tex: int = 200, every: int = 25, lr_pos: float = 0.01,
+            lr_tex: float = 0.01, lap0: float = 10.0, lap_gamma: float = 0.99, time_reps: int = 50) -> dict:
+    """Runs the fit and returns its curve and timings.  The timing replays
+    run after the curve on copies of the final state, so they do not change
+    the reported fit."""
+    st = Step(scene, target=make_target(scene))
+    fl = FitLoop(st, lr_pos=lr_pos, lr_tex=lr_tex, lap0=lap0, lap_gamma=lap_gamma)
+    tree = cKDTree(surface_samples(scene.target_pos, scene.tris))
+    curve = []
+
+    def record(stage, it):
+        torch.cuda.synchronize()
+        curve.append({"stage": stage, "iteration": it, "sil_l2": round(_sil_l2(st), 6),
+                      "color_l2": round(_col_l2(st), 6),
+                      "surface_distance": round(mean_surface_distance(st.pos.cpu().numpy(), tree), 5),
+                      "laplacian": round(float(fl.reg.item()), 6)})
+
+    st.forward()
+    record("silhouette", 0)
+    g_sil = _capture(fl.silhouette_iteration)
+    done = 1
+    while done < n_sil:
+        k = min(every - done % every, n_sil - done)
+        for _ in range(k):
+            g_sil.replay()
+        done += k
+        if done % every == 0 or done == n_sil:
+            st.forward()
+            record("silhouette", done)
+    fl.start_texture_stage()
+    fl.ts.forward()
+    record("texture", 0)
+    g_tex = _capture(fl.texture_iteration)
+    done = 1
+    while done < n_tex:
+        k = min(every - done % every, n_tex - done)
+        for _ in range(k):
+            g_tex.replay()
+        done += k
+        if done % every == 0 or done == n_tex:
+            fl.ts.forward()
+            record("texture", done)
+    status = st.ctx.check_status()
+    # timing: replays on the fitted state (positions and texture saved and restored)
+    saved = (st.pos.clone(), st.tex.clone(), fl.adam_pos.m.clone(), fl.adam_pos.v.clone(),
+             fl.adam_pos.state.clone(), fl.adam_tex.m.clone(), fl.adam_tex.v.clone(), fl.adam_tex.state.clone())
+    ms_sil = _time(g_sil, time_reps)
+    ms_tex = _time(g_tex, time_reps)
+    for dst, src in zip((st.pos, st.tex, fl.adam_pos.m, fl.adam_pos.v, fl.adam_pos.state, fl.adam_tex.m,
+                         fl.adam_tex.v, fl.adam_tex.state), saved):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    return {"workload": scene.name, "views": int(st.B), "H": st.H, "W": st.W, "triangles": int(st.T),
+            "K": st.K, "r": st.r, "lr_pos": lr_pos, "lr_tex": lr_tex, "lap0": lap0, "lap_gamma": lap_gamma,
+            "iterations": {"silhouette": n_sil, "texture": n_tex}, "bin_overflow": status != 0,
+            "ms_per_iteration": {"silhouette": round(ms_sil, 4), "texture": round(ms_tex, 4)},
+            "curve": curve}

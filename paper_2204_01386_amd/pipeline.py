@@ -811,3 +811,77 @@ def autotune_streams(step, reps: int = 20) -> dict:
         del g
     step.concurrent = min(results, key=results.get)
     return {"concurrent": step.concurrent, "ms": results}
+
+
+# ---------------------------------------------------------------------------
+# the optimisation loop
+# ---------------------------------------------------------------------------
+class Adam:
+    """Adam (Kingma & Ba) on one parameter tensor: moments and the step state
+    live on the device, so a captured step replays successive updates."""
+
+    def __init__(self, param: torch.Tensor, lr: float, betas=(0.9, 0.999), eps: float = 1e-8):
+        self.p = param
+        self.lr, self.b1, self.b2, self.eps = float(lr), float(betas[0]), float(betas[1]), float(eps)
+        self.m = torch.zeros_like(param)
+        self.v = torch.zeros_like(param)
+        self.state = Bd.adam_state(param.device)
+
+    def step(self, ctx, grad: torch.Tensor, stream):
+        rc = _lib.dressi_adam(ctx.handle, _p(self.p), _p(grad), _p(self.m), _p(self.v), self.p.numel(), self.lr,
+                              self.b1, self.b2, self.eps, _p(self.state), stream)
+        if rc != 0:
+            ctx.check(rc, "adam")
+
+    def steps_taken(self) -> int:
+        return int(self.state[0].item())
+
+
+class FitLoop:
+    """The paper's two-stage fit (§4.1, the cross-platform application):
+    first the vertex positions, from silhouettes (the image loss's colour
+    gradient dropped) plus the scheduled Laplacian regulariser, then, on the
+    fitted geometry, the albedo texture from the colour loss, both with Adam.
+    The texture stage runs as a texture-only step (TextureStep: the
+    rasterization and the inverse-UV map cached).  Every iteration allocates
+    nothing and can be captured into a graph; the Adam states and the
+    regulariser's schedule advance on the device."""
+
+    def __init__(self, step: Step, lr_pos: float = 0.01, lr_tex: float = 0.01, lap0: float = 10.0,
+                 lap_gamma: float = 0.99):
+        self.st = step
+        # the geometry moves during the fit: give every tile bin room for all
+        # triangles when that is affordable, so no bin can overflow
+        nt = ((step.H + 15) // 16) * ((step.W + 15) // 16)
+        cap = 1 << max(0, (step.T - 1).bit_length())
+        if step.B * nt * cap * 4 <= 1 << 30:
+            step.ctx.reserve(0, cap)
+        self.adam_pos = Adam(step.pos, lr_pos)
+        self.adam_tex = Adam(step.tex, lr_tex) if step.tex is not None else None
+        self.lap0, self.lap_gamma = float(lap0), float(lap_gamma)
+        self.reg = torch.zeros(1, device=step.dev)
+        self.ts = None
+
+    def silhouette_iteration(self):
+        st = self.st
+        h, s = st.ctx.handle, st._s()
+        st.forward()
+        st.loss_and_grad()
+        st.g_color.zero_()
+        st.backward()
+        st._chk(_lib.dressi_laplacian_reg(h, _p(st.pos), _p(st.tris), st.V, st.T, _p(st.adj), self.lap0,
+                                          self.lap_gamma, _p(self.adam_pos.state), _p(st.g_pos), _p(st.g_pos),
+                                          _p(self.reg), s), "laplacian_reg")
+        self.adam_pos.step(st.ctx, st.g_pos, s)
+
+    def start_texture_stage(self):
+        """Caches the fitted geometry for the texture stage."""
+        if self.ts is None:
+            self.ts = TextureStep(self.st)
+        else:
+            self.ts.refresh()
+
+    def texture_iteration(self):
+        st = self.st
+        self.ts.run()
+        self.adam_tex.step(st.ctx, st.g_tex, st._s())

@@ -546,3 +546,32 @@ def sphere_tangents(pos: np.ndarray):
     direction of growing u of the spherical UVs (orthogonalised per pixel)."""
     phi = np.arctan2(pos[:, 2].astype(np.float64), pos[:, 0].astype(np.float64))
     return np.stack([-np.sin(phi), np.zeros_like(phi), np.cos(phi)], -1).astype(np.float32)
+
+
+def pear_surface(d: np.ndarray) -> np.ndarray:
+    """A smooth pear-like closed surface over unit directions d [N,3]: a
+    radius that narrows towards +y, a wider bulb towards -y, stretched along y."""
+    y = d[:, 1]
+    rad = 0.62 - 0.16 * y + 0.10 * np.cos(2.4 * (y + 0.35)) + 0.04 * d[:, 0] * d[:, 2]
+    p = d * rad[:, None]
+    p[:, 1] = 1.3 * p[:, 1] + 0.27    # centred on the origin
+    return p
+
+
+def fit_scene(seed: int = 0, subdiv: int = 4, H: int = 256, tex_size: int = 256, n_views: int = 6,
+              K: int = 2, r: float = 0.01) -> Scene:
+    """The optimisation workload of the paper's cross-platform application
+    (§4.1): a white sphere with a white albedo texture fitted to images of a
+    pear, in 6 views of 256^2 with a 256^2 albedo texture.  The pear here is
+    synthetic: the same icosphere topology mapped onto `pear_surface`, with a
+    value-noise albedo.  HardSoftRas K = 2, r = 0.01, sigma = r/7, delta = r
+    (the listing's parameters); Phong; cameras on the ring of config 3."""
+    p, tris = icosphere(subdiv)
+    uv, uv_tris = spherical_uv(p.astype(np.float32), tris)
+    start = (0.7 * p).astype(np.float32)
+    target = pear_surface(p).astype(np.float32)
+    white = np.ones((tex_size, tex_size, 4), np.float32)
+    eyes = camera_ring(n_views, seed)
+    return Scene(f"fit-sphere{subdiv}-to-pear-{n_views}x{H}", start, tris, view_proj(eyes), eyes.astype(np.float32),
+                 H, H, K, r, "phong", uv=uv, uv_tris=uv_tris, tex=white, target_pos=target,
+                 target_tex=value_noise(tex_size, tex_size, 4, seed + 3))

@@ -366,6 +366,45 @@ def test_softras(B, mode):
         assert_grad_close(host(gd), gd_o, what="grad_dist")
 
 
+def test_softras_saturated_sigmoids(B):
+    """Layers whose sigmoid is within 1e-7..1e-3 of 0 or 1 (|dist| / sigma
+    in 7..16): the silhouette's product of complements and the distance
+    gradient w (1 - w) / sigma keep their relative precision (a complement
+    taken as 1 - w in float32 would lose it)."""
+    rng = np.random.default_rng(11)
+    Bv, K, H, W = 2, 3, 24, 40
+    sigma = 0.01 / 7
+    tid = rng.integers(0, 50, (Bv, K, H, W)).astype(np.int32)
+    tid[:, 2, :, ::3] = -1
+    x = rng.uniform(7.0, 16.0, (Bv, K, H, W)) * rng.choice([-1.0, 1.0], (Bv, K, H, W))
+    dist = (x * sigma).astype(np.float32)
+    col = rng.random((Bv, K, H, W, 3)).astype(np.float32)
+    mode = oracle.BLEND_SOFTRAS   # every pixel blended
+    oc_o, os_o, E_o = oracle.softras(col, dist, tid, sigma, 0.0, mode)
+    oc, os_, E = B.dressi_softras(dev(col), dev(dist), dev(tid), sigma, 0.0, mode)
+    assert_vals_close(host(oc), oc_o, what="color")
+    # 1 - silhouette = the product of complements, checked relatively
+    qo, q = 1.0 - os_o, 1.0 - host(os_).astype(np.float64)
+    big = qo > 1e-3
+    assert (np.abs(q - qo)[big] <= 1e-5 * qo[big]).all()
+    gc = rng.standard_normal(oc_o.shape).astype(np.float32)
+    gs = rng.standard_normal(os_o.shape).astype(np.float32)
+    gl_o, gd_o = oracle.softras_bwd(col, dist, tid, sigma, E_o, gc, gs)
+    gl, gd = B.dressi_softras_bwd(dev(col), dev(dist), dev(tid), sigma, E, dev(gc), dev(gs))
+    assert_grad_close(host(gl), gl_o, what="grad_layer_color")
+    assert_grad_close(host(gd), gd_o, what="grad_dist")
+    # the silhouette's gradient alone is a product per layer (no sum that can
+    # cancel): every element within 1e-5 relative
+    z = np.zeros_like(gc)
+    _, gd_o = oracle.softras_bwd(col, dist, tid, sigma, E_o, z, gs)
+    _, gd = B.dressi_softras_bwd(dev(col), dev(dist), dev(tid), sigma, E, dev(z), dev(gs))
+    gd = host(gd).astype(np.float64)
+    nz = gd_o != 0
+    assert nz.sum() > 1000
+    rel = np.abs(gd - gd_o)[nz] / np.abs(gd_o)[nz]
+    assert rel.max() <= 1e-5, rel.max()
+
+
 def test_softras_hard_only_no_dist(B):
     pc, tris = sphere_scene(subdiv=3)
     tid_o, _, _, _ = oracle.rasterize(pc, tris, 64, 64)
