@@ -59,6 +59,8 @@ def parse():
     ap.add_argument("--no-uneven", dest="uneven", action="store_false",
                     help="skip the 64-instance uneven batch measurement")
     ap.add_argument("--uneven-steps", type=int, default=20)
+    ap.add_argument("--kr-sweep", action="store_true",
+                    help="only the K x r sweep of the sphere-to-pear silhouette fit (one JSON line)")
     ap.add_argument("--no-fit", dest="fit", action="store_false",
                     help="skip the two-stage fit (sphere to pear, positions then texture)")
     ap.add_argument("--copy-ref", type=int, default=0, metavar="MIB",
@@ -530,6 +532,10 @@ def main():
     if args.paper_table:
         print(json.dumps({"paper_table": paper_table(min(args.steps, 50), min(args.warmup, 5)),
                           "note": "white Lambert spheres here, silhouette shading in the paper; context only"}))
+        return
+    if args.kr_sweep:
+        from paper_2204_01386_amd.fit import kr_sweep
+        print(json.dumps({"kr_sweep": kr_sweep()}))
         return
     if args.copy_ref:
         src = torch.ones(args.copy_ref * (1 << 18), dtype=torch.float32, device="cuda")

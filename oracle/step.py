@@ -70,7 +70,10 @@ def forward(scene, views=None, target=False):
         st.update(shade_n=shade_n, dir=d, env_s=env_s)
     col = O.shade(mode, shade_n, p if mode != O.SHADE_LAMBERT else None, albedo, env_s, eye, tid)
     sigma = r / 7.0 if r > 0 else 1.0
-    blend = O.BLEND_HSR if r > 0 else O.BLEND_HARD
+    # the blend setting of §3.4.3: HardSoftRas with delta = r by default; a
+    # scene may choose the anti-aliasing or SoftRas-like settings instead
+    blend = {"hsr": O.BLEND_HSR, "aa": O.BLEND_AA, "softras": O.BLEND_SOFTRAS,
+             "hard": O.BLEND_HARD}[scene.extra.get("blend", "hsr" if r > 0 else "hard")]
     oc, os_, E = O.softras(col, st["dist"], tid, sigma, r, blend)
     st.update(layer_color=col, albedo=albedo, color=oc, sil=os_, E=E, sigma=sigma)
     st["rgba"] = np.concatenate([oc, os_[..., None]], -1)

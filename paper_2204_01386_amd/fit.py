@@ -115,3 +115,40 @@ def run_fit(scene: Scene, n_sil: int = 300, n_tex: int = 200, every: int = 25, l
             "iterations": {"silhouette": n_sil, "texture": n_tex}, "bin_overflow": status != 0,
             "ms_per_iteration": {"silhouette": round(ms_sil, 4), "texture": round(ms_tex, 4)},
             "curve": curve}
+
+
+def kr_sweep(Ks=(1, 2, 3, 4, 5), r_px=(1, 2, 3, 5, 7), checkpoints=(50, 300), seed: int = 0,
+             blend: str = "hsr") -> dict:
+    """The paper's validation of HardSoftRas settings (§4.2: a heatmap over K
+    and r of the fitted geometry's distance to the target, early and late in
+    the optimisation) on the sphere-to-pear silhouette fit: for every (K, r)
+    the target is rendered with the same setting, and the mean distance of
+    the fitted vertices to the target surface is recorded at each checkpoint
+    (iterations of the silhouette stage)."""
+    out = {"checkpoints": list(checkpoints), "K": list(Ks), "r_px": list(r_px), "blend": blend,
+           "surface_distance": {}, "ms_per_iteration": {}}
+    base = None
+    for K in Ks:
+        for rp in r_px:
+            from .scenes import fit_scene
+            scene = fit_scene(seed, K=K, r=rp / 256.0, blend=blend)
+            if base is None:
+                base = cKDTree(surface_samples(scene.target_pos, scene.tris))
+            st = Step(scene, target=make_target(scene))
+            fl = FitLoop(st)
+            g = _capture(fl.silhouette_iteration)
+            done, dists = 1, []
+            for cp in checkpoints:
+                for _ in range(cp - done):
+                    g.replay()
+                done = cp
+                torch.cuda.synchronize()
+                dists.append(round(mean_surface_distance(st.pos.cpu().numpy(), base), 5))
+            key = f"K={K},r={rp}px"
+            out["surface_distance"][key] = dists
+            out["ms_per_iteration"][key] = round(_time(g, 20), 4)
+            if st.ctx.check_status() != 0:
+                out.setdefault("bin_overflow", []).append(key)
+            del g, fl, st
+            torch.cuda.empty_cache()
+    return out

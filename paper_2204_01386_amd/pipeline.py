@@ -130,7 +130,15 @@ class Step(_TwoStreams):
             self.pos = f32(scene.pos)
         self.mode = {"lambert": Bd.SHADE_LAMBERT, "phong": Bd.SHADE_PHONG,
                      "phong_env": Bd.SHADE_PHONG_ENV}[scene.shading]
-        self.blend = Bd.BLEND_HSR if self.r > 0 else Bd.BLEND_HARD
+        # HardSoftRas blend (§3.4.3): the paper's setting (edge band of width
+        # delta = r, sigma = r / 7), or a scene's choice among its other
+        # settings: "aa" (edge mask = the silhouette boundary, delta of one
+        # pixel), "softras" (every pixel blended), "hard" (no blending)
+        blend = scene.extra.get("blend", "hsr" if self.r > 0 else "hard")
+        self.blend = {"hsr": Bd.BLEND_HSR, "aa": Bd.BLEND_AA, "softras": Bd.BLEND_SOFTRAS,
+                      "hard": Bd.BLEND_HARD}[blend]
+        if self.blend != Bd.BLEND_HARD and self.r <= 0:
+            raise ValueError(f"blend {blend!r} needs a soft reach r > 0")
         self.sigma = self.r / 7.0 if self.r > 0 else 1.0
         self.delta = self.r
         # per-vertex attributes: normal, position, extra (colour or tangent)

@@ -559,13 +559,14 @@ def pear_surface(d: np.ndarray) -> np.ndarray:
 
 
 def fit_scene(seed: int = 0, subdiv: int = 4, H: int = 256, tex_size: int = 256, n_views: int = 6,
-              K: int = 2, r: float = 0.01) -> Scene:
+              K: int = 2, r: float = 0.01, blend: str = "hsr") -> Scene:
     """The optimisation workload of the paper's cross-platform application
     (§4.1): a white sphere with a white albedo texture fitted to images of a
     pear, in 6 views of 256^2 with a 256^2 albedo texture.  The pear here is
     synthetic: the same icosphere topology mapped onto `pear_surface`, with a
     value-noise albedo.  HardSoftRas K = 2, r = 0.01, sigma = r/7, delta = r
-    (the listing's parameters); Phong; cameras on the ring of config 3."""
+    (the listing's parameters); Phong; cameras on the ring of config 3.
+    `blend` picks another setting of the blend ("aa", "softras")."""
     p, tris = icosphere(subdiv)
     uv, uv_tris = spherical_uv(p.astype(np.float32), tris)
     start = (0.7 * p).astype(np.float32)
@@ -574,4 +575,4 @@ def fit_scene(seed: int = 0, subdiv: int = 4, H: int = 256, tex_size: int = 256,
     eyes = camera_ring(n_views, seed)
     return Scene(f"fit-sphere{subdiv}-to-pear-{n_views}x{H}", start, tris, view_proj(eyes), eyes.astype(np.float32),
                  H, H, K, r, "phong", uv=uv, uv_tris=uv_tris, tex=white, target_pos=target,
-                 target_tex=value_noise(tex_size, tex_size, 4, seed + 3))
+                 target_tex=value_noise(tex_size, tex_size, 4, seed + 3), extra={"blend": blend})

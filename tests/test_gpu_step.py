@@ -186,6 +186,14 @@ def test_step_config3_two_views(B):
     _compare_step(s, views=slice(0, 2), env_tol=2e-2, img_tol=5e-5, kink_tol=True)
 
 
+@pytest.mark.parametrize("blend,K,r", [("aa", 1, 2 / 128), ("softras", 3, 0.02), ("hsr", 2, 0.01)])
+def test_step_blend_settings(B, blend, K, r):
+    """The blend's other settings (§3.4.3) through the whole step against the
+    oracle: anti-aliasing (edge mask = the silhouette boundary, K = 1) and
+    SoftRas-like (every pixel blended), beside the paper's own setting."""
+    _compare_step(scenes.fit_scene(subdiv=3, H=128, K=K, r=r, blend=blend))
+
+
 @pytest.mark.parametrize("concurrent", [False, True])
 def test_step_deterministic_and_graph_replay(B, concurrent):
     """The step is bitwise reproducible, also with its independent branches
