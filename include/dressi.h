@@ -420,6 +420,91 @@ int dressi_laplacian_reg(dressi_ctx *ctx, const float *pos, const int32_t *tris,
                          const int32_t *adj, float lam0, float gamma, const void *adam_state,
                          const float *grad_in, float *grad_out, float *value, void *stream);
 
+/* ----------------------------------------------------------------------------
+ * Physically-based shading with image-based lighting (the render graph of
+ * appendix B: irradiance, prefiltered environment and BRDF integration maps
+ * built from the environment image, then split-sum PBS; appendix C
+ * optimises an environment map and the roughness with it).
+ *
+ * Cube maps are [6,S,S,3] float (faces +X,-X,+Y,-Y,+Z,-Z, the sampler's
+ * convention).  Texel (f, row j, column i) has centre (a, b) =
+ * (2(i+1/2)/S - 1, 2(j+1/2)/S - 1) on its face and its exact solid angle.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    int S;    /* environment face size (1..1024)                       */
+    int Si;   /* irradiance face size                                  */
+    int Sp;   /* prefiltered face size                                 */
+    int L;    /* prefiltered levels (2..16): roughness l/(L-1), GGX
+                 alpha max(roughness^2, 1e-3)                          */
+} dressi_ibl_desc;
+
+/* dressi_ibl_filter: env [6,S,S,3] -> irr [6,Si,Si,3], the cosine
+ * convolution sum_j env_j max(0, n.w_j) O_j / sum_j max(0, n.w_j) O_j over
+ * every environment texel j (direction w_j, solid angle O_j); pref
+ * [L,6,Sp,Sp,3], level l the GGX convolution with n = v = R:
+ * sum_j env_j W_j / sum_j W_j, W_j = max(0, R.w_j) D(h_j) O_j.  norm (device,
+ * dressi_ibl_norm_bytes) receives every output's denominator, for the
+ * backward.  Sums in double.
+ * dressi_ibl_filter_bwd: grad_env [6,S,S,3] = the exact adjoint, each
+ * environment texel gathering sum_o grad_o K_oj / norm_o over every output
+ * (no atomics, fixed order). */
+size_t dressi_ibl_norm_bytes(const dressi_ibl_desc *d);
+int dressi_ibl_filter(dressi_ctx *ctx, const float *env, const dressi_ibl_desc *d, float *irr,
+                      float *pref, double *norm, void *stream);
+int dressi_ibl_filter_bwd(dressi_ctx *ctx, const dressi_ibl_desc *d, const double *norm,
+                          const float *grad_irr, const float *grad_pref, float *grad_env,
+                          void *stream);
+
+/* BRDF integration table lut [N,N,2] (rows: roughness (j+1/2)/N, columns:
+ * n.v (i+1/2)/N) of the split sum's scale and bias (A, B): the mean over the
+ * M-point Hammersley set (base-2 radical inverse) of GGX-sampled half
+ * vectors, Smith G with k = alpha/2, Fresnel weight (1 - v.h)^5. */
+int dressi_brdf_lut(dressi_ctx *ctx, int N, int M, float *lut, void *stream);
+
+typedef struct {
+    const float *normal; int normal_stride;   /* interpolated normal (renormalised) */
+    const float *pos; int pos_stride;         /* world position                     */
+    const float *albedo; int albedo_stride;   /* rgb                                */
+    const float *irr; int irr_stride;         /* irradiance sampled along dir_n     */
+    const float *pref; int pref_stride;       /* level l sampled along dir_r at     */
+    int64_t pref_level_stride;                /*   pref + l * pref_level_stride     */
+    const float *material;                    /* device [2]: metallic, roughness    */
+    const float *lut; int lut_n;              /* dressi_brdf_lut table              */
+    int levels;                               /* L of the prefiltered map           */
+} dressi_pbs_in;
+
+typedef struct {
+    float *normal; int normal_stride;
+    float *pos; int pos_stride;
+    float *albedo; int albedo_stride;
+    float *irr;       /* [N,3]                                                   */
+    float *pref;      /* [L,N,3]: every level, 0 off the two the roughness uses  */
+    float *material;  /* device [2], summed over the fragments in a fixed order  */
+} dressi_pbs_grad;
+
+/* Split-sum shading of N = B*Npv fragments (view b = i / Npv, eye[b]):
+ *   n' = normalize(n), v = normalize(eye - p), c = max(n'.v, 1e-4),
+ *   dir_n = n', dir_r = R = 2 (n'.v) n' - v,
+ *   F0 = 0.04 (1 - m) + a m,  F = F0 + (max(1 - r, F0) - F0)(1 - c)^5,
+ *   x = r (L-1), l0 = min(floor x, L-2), f = x - l0,
+ *   P = (1 - f) pref_l0 + f pref_l0+1,  (A, B) = lut bilinear (clamped) at (c, r),
+ *   C = (1 - F)(1 - m) a irr + P (F0 A + B),  color = C / (1 + C).
+ * Writes, when non-NULL: dir_n, dir_r [N,3] and level_tri_id [L,N] (tri_id
+ * where level l is one of the two in use, else -1: the masks for sampling
+ * and differentiating each prefiltered level); then color [N,3] (needs
+ * the samples).  Fragments with tri_id < 0 give 0. */
+int dressi_shade_pbs(dressi_ctx *ctx, const dressi_pbs_in *in, const float *eye,
+                     const int32_t *tri_id, int B, int64_t Npv, float *color, float *dir_n,
+                     float *dir_r, int32_t *level_tri_id, void *stream);
+/* Backward of dressi_shade_pbs w.r.t. every non-NULL member of grad.  The
+ * normal and position gradients include the lookups' direction gradients
+ * grad_dir_n [N,3] and grad_dir_r [L,N,3] (summed over levels; NULL = 0);
+ * the others do not depend on them, so they can be taken first. */
+int dressi_shade_pbs_bwd(dressi_ctx *ctx, const dressi_pbs_in *in, const float *eye,
+                         const int32_t *tri_id, int B, int64_t Npv, const float *grad_color,
+                         const float *grad_dir_n, const float *grad_dir_r,
+                         const dressi_pbs_grad *grad, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

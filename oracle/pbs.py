@@ -258,3 +258,61 @@ def dirs_vjp(n, p, eye, g_dir_n, g_dir_r):
 def cube_sample(tex, d, tri_id):
     """The oracle's bilinear cube lookup (float32 directions, as the kernels get them)."""
     return O.texture(tex, np.asarray(d, np.float32), tri_id, kind=O.TEX_CUBE)
+
+
+# ---------------------------------------------------------------------------
+# the whole PBS step on fixed geometry
+# ---------------------------------------------------------------------------
+def pbs_forward(scene, env, material, tex, Si, Sp, L, lut):
+    """Geometry from the oracle's step (rasterization, G-buffer, UVs), then
+    the filters, lookups, shading and blend.  Returns the state dict."""
+    from oracle import step as ostep
+    g = ostep.forward(scene)
+    tid = g["tid"]
+    Bv, K, H, W = tid.shape
+    gb = g["gbuf"]
+    n, p = gb[..., 0:3], gb[..., 3:6]
+    wu, wv = scene.extra.get("wrap", (O.WRAP_REPEAT, O.WRAP_CLAMP))
+    albedo = O.texture(tex, g["uv"], tid, wrap_u=wu, wrap_v=wv)[..., 0:3]
+    irr, pref = ibl_filter(env, Si, Sp, L)
+    eye = np.broadcast_to(np.asarray(scene.eyes, np.float64)[:, None, None, None, :], n.shape)
+    cov = tid >= 0
+    # lookup directions in double, handed to the sampler in float32
+    nsafe = np.where(cov[..., None], n, 1.0)
+    with torch.no_grad():
+        nn, R = pbs_dirs(torch.tensor(nsafe), torch.tensor(p), torch.tensor(np.ascontiguousarray(eye)))
+    dn = np.where(cov[..., None], nn.numpy(), 0.0).astype(np.float32)
+    dr = np.where(cov[..., None], R.numpy(), 0.0).astype(np.float32)
+    m, r = float(material[0]), float(material[1])
+    l0 = min(int(math.floor(r * (L - 1))), L - 2)
+    tid_l = [np.where(cov, tid, -1) if l in (l0, l0 + 1) else np.full_like(tid, -1) for l in range(L)]
+    irr_s = cube_sample(irr, dn, tid)
+    pref_s = np.stack([cube_sample(pref[l], dr, tid_l[l]) for l in range(L)])
+    out, _ = shade_and_grads(nsafe, p, eye, albedo, m, r, irr_s, pref_s, lut, L, tid, np.zeros(n.shape))
+    blend = {"hsr": O.BLEND_HSR, "aa": O.BLEND_AA, "softras": O.BLEND_SOFTRAS,
+             "hard": O.BLEND_HARD}[scene.extra.get("blend", "hsr" if scene.r > 0 else "hard")]
+    oc, os_, E = O.softras(out, g["dist"], tid, g["sigma"], float(scene.r), blend)
+    return {"geo": g, "tid": tid, "tid_l": tid_l, "n": nsafe, "p": p, "eye": eye, "albedo": albedo, "irr": irr,
+            "pref": pref, "dn": dn, "dr": dr, "irr_s": irr_s, "pref_s": pref_s, "layer": out, "color": oc,
+            "sil": os_, "E": E, "rgba": np.concatenate([oc, os_[..., None]], -1), "m": m, "r": r}
+
+
+def pbs_step(scene, env, material, tex, target_rgba, Si, Sp, L, lut):
+    """Forward, L2 loss against target_rgba, and the gradients of the
+    environment map, the material and the albedo texture."""
+    f = pbs_forward(scene, env, material, tex, Si, Sp, L, lut)
+    tid = f["tid"]
+    loss, g_c, g_s = O.loss_l2(f["color"], f["sil"], target_rgba)
+    gl, _ = O.softras_bwd(f["layer"], f["geo"]["dist"], tid, f["geo"]["sigma"], f["E"], g_c, g_s)
+    _, gr = shade_and_grads(f["n"], f["p"], f["eye"], f["albedo"], f["m"], f["r"], f["irr_s"], f["pref_s"], lut, L,
+                            tid, gl)
+    S = tid.shape[0] * tid.shape[1]
+    rs = lambda a: a.reshape((S,) + a.shape[2:])
+    g_irr = O.texture_bwd_tex(f["irr"].shape, rs(f["dn"]), rs(tid), rs(gr["irr_s"]), kind=O.TEX_CUBE)
+    g_pref = np.stack([O.texture_bwd_tex(f["pref"][l].shape, rs(f["dr"]), rs(f["tid_l"][l]), rs(gr["pref_s"][l]),
+                                         kind=O.TEX_CUBE) for l in range(L)])
+    g_env = ibl_filter_bwd(env.shape[1], Si, Sp, L, g_irr, g_pref)
+    wu, wv = scene.extra.get("wrap", (O.WRAP_REPEAT, O.WRAP_CLAMP))
+    g_samp = np.concatenate([gr["albedo"], np.zeros(gr["albedo"].shape[:-1] + (1,))], -1)
+    g_tex = O.texture_bwd_tex(tex.shape, rs(f["geo"]["uv"]), rs(tid), rs(g_samp), wrap_u=wu, wrap_v=wv)
+    return f, {"loss": loss, "env": g_env, "material": np.array([gr["metallic"], gr["roughness"]]), "tex": g_tex}

@@ -55,6 +55,26 @@ class FragGrad(C.Structure):
     _fields_ = [("normal", _vp), ("normal_stride", _i), ("pos", _vp), ("pos_stride", _i),
                 ("tangent", _vp), ("tangent_stride", _i), ("nmap", _vp), ("nmap_stride", _i),
                 ("albedo", _vp), ("albedo_stride", _i), ("env", _vp), ("env_stride", _i)]
+
+
+class IblDesc(C.Structure):
+    """dressi_ibl_desc: environment, irradiance and prefiltered face sizes, levels."""
+    _fields_ = [("S", _i), ("Si", _i), ("Sp", _i), ("L", _i)]
+
+
+class PbsIn(C.Structure):
+    """dressi_pbs_in: per-fragment PBS inputs as (pointer, row stride)."""
+    _fields_ = [("normal", _vp), ("normal_stride", _i), ("pos", _vp), ("pos_stride", _i),
+                ("albedo", _vp), ("albedo_stride", _i), ("irr", _vp), ("irr_stride", _i),
+                ("pref", _vp), ("pref_stride", _i), ("pref_level_stride", _i64),
+                ("material", _vp), ("lut", _vp), ("lut_n", _i), ("levels", _i)]
+
+
+class PbsGrad(C.Structure):
+    _fields_ = [("normal", _vp), ("normal_stride", _i), ("pos", _vp), ("pos_stride", _i),
+                ("albedo", _vp), ("albedo_stride", _i), ("irr", _vp), ("pref", _vp), ("material", _vp)]
+
+
 _SIG = {
     "dressi_create": [C.POINTER(C.c_void_p), _i],
     "dressi_destroy": [_vp],
@@ -68,6 +88,11 @@ _SIG = {
                                _vp, _vp, _vp, _vp, _vp],
     "dressi_texture": [_vp, _vp, C.POINTER(TexDesc), _vp, _vp, _i, _i, _i, _vp, _vp],
     "dressi_texture_bwd": [_vp, _vp, C.POINTER(TexDesc), _vp, _vp, _i, _i, _i, _vp, _vp, _vp, _vp],
+    "dressi_ibl_filter": [_vp, _vp, C.POINTER(IblDesc), _vp, _vp, _vp, _vp],
+    "dressi_ibl_filter_bwd": [_vp, C.POINTER(IblDesc), _vp, _vp, _vp, _vp, _vp],
+    "dressi_brdf_lut": [_vp, _i, _i, _vp, _vp],
+    "dressi_shade_pbs": [_vp, C.POINTER(PbsIn), _vp, _vp, _i, _i64, _vp, _vp, _vp, _vp, _vp],
+    "dressi_shade_pbs_bwd": [_vp, C.POINTER(PbsIn), _vp, _vp, _i, _i64, _vp, _vp, _vp, C.POINTER(PbsGrad), _vp],
     "dressi_adam": [_vp, _vp, _vp, _vp, _vp, _i64, _f, _f, _f, _f, _vp, _vp],
     "dressi_laplacian_reg": [_vp, _vp, _vp, _i, _i, _vp, _f, _f, _vp, _vp, _vp, _vp, _vp],
     "dressi_invuv_build": [_vp, C.POINTER(TexDesc), _vp, _vp, _i, _i, _i, _vp, _vp],
@@ -98,6 +123,8 @@ _lib.dressi_last_error.argtypes = [_vp]
 _lib.dressi_last_error.restype = C.c_char_p
 _lib.dressi_scratch_bytes.argtypes = [_i, _i, _i, _i, _i, _i, _f, _i, _i, _i64, _i]
 _lib.dressi_scratch_bytes.restype = C.c_size_t
+_lib.dressi_ibl_norm_bytes.argtypes = [C.POINTER(IblDesc)]
+_lib.dressi_ibl_norm_bytes.restype = C.c_size_t
 _lib.dressi_invuv_bytes.argtypes = [C.POINTER(TexDesc), _i]
 _lib.dressi_invuv_bytes.restype = C.c_size_t
 _lib.dressi_fragment_index_bytes.argtypes = [_i, _i, _i, _i, _i]
@@ -108,7 +135,8 @@ _lib.dressi_profile_read.argtypes = [C.POINTER(C.c_char_p), C.POINTER(C.c_float)
 _lib.dressi_profile_read.restype = C.c_int
 
 EXPORTED = sorted(list(_SIG) + ["dressi_last_error", "dressi_scratch_bytes", "dressi_fragment_index_bytes",
-                                "dressi_invuv_bytes", "dressi_profile_start", "dressi_profile_read"])
+                                "dressi_invuv_bytes", "dressi_ibl_norm_bytes", "dressi_profile_start",
+                                "dressi_profile_read"])
 
 
 class DressiError(RuntimeError):
@@ -348,6 +376,56 @@ def dressi_texture_grad_invuv(tex, coord, tri_id, inv, grad_out, kind=TEX_2D, wr
                                              _ptr(inv), _ptr(grad_out), _ptr(gt), _stream()),
               "dressi_texture_grad_invuv")
     return gt
+
+
+def dressi_ibl_filter(env, Si, Sp, L):
+    """env [6,S,S,3] -> (irr [6,Si,Si,3], pref [L,6,Sp,Sp,3], norm float64)."""
+    _need(env, torch.float32, "env")
+    S = env.shape[1]
+    d = IblDesc(S, Si, Sp, L)
+    dev = env.device
+    irr = torch.empty((6, Si, Si, 3), dtype=torch.float32, device=dev)
+    pref = torch.empty((L, 6, Sp, Sp, 3), dtype=torch.float32, device=dev)
+    norm = torch.empty(int(_lib.dressi_ibl_norm_bytes(C.byref(d))) // 8, dtype=torch.float64, device=dev)
+    ctx = context(dev.index)
+    ctx.check(_lib.dressi_ibl_filter(ctx.handle, _ptr(env), C.byref(d), _ptr(irr), _ptr(pref), _ptr(norm),
+                                     _stream()), "dressi_ibl_filter")
+    return irr, pref, norm
+
+
+def dressi_ibl_filter_bwd(S, norm, grad_irr, grad_pref):
+    Si, L, Sp = grad_irr.shape[1], grad_pref.shape[0], grad_pref.shape[2]
+    d = IblDesc(S, Si, Sp, L)
+    g = torch.empty((6, S, S, 3), dtype=torch.float32, device=grad_irr.device)
+    ctx = context(grad_irr.device.index)
+    ctx.check(_lib.dressi_ibl_filter_bwd(ctx.handle, C.byref(d), _ptr(norm), _ptr(grad_irr), _ptr(grad_pref),
+                                         _ptr(g), _stream()), "dressi_ibl_filter_bwd")
+    return g
+
+
+def dressi_brdf_lut(N, M, device=None):
+    lut = torch.empty((N, N, 2), dtype=torch.float32, device=device or "cuda")
+    ctx = context(lut.device.index)
+    ctx.check(_lib.dressi_brdf_lut(ctx.handle, N, M, _ptr(lut), _stream()), "dressi_brdf_lut")
+    return lut
+
+
+def pbs_in(normal, pos, material, lut, albedo=None, irr=None, pref=None, levels=None):
+    """A dressi_pbs_in over [N,3] rows (pref [L,N,3]); keeps no references."""
+    pin = PbsIn()
+    pin.normal, pin.normal_stride = _ptr(normal), normal.shape[-1]
+    pin.pos, pin.pos_stride = _ptr(pos), pos.shape[-1]
+    if albedo is not None:
+        pin.albedo, pin.albedo_stride = _ptr(albedo), albedo.shape[-1]
+    if irr is not None:
+        pin.irr, pin.irr_stride = _ptr(irr), 3
+    if pref is not None:
+        pin.pref, pin.pref_stride = _ptr(pref), 3
+        pin.pref_level_stride = pref[0].numel()
+    pin.material = _ptr(material)
+    pin.lut, pin.lut_n = _ptr(lut), lut.shape[0]
+    pin.levels = levels if levels is not None else (pref.shape[0] if pref is not None else 2)
+    return pin
 
 
 ADAM_STATE_BYTES = 16

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdressi.so")
 SOURCES = ["context.hip", "prims.hip", "raster.hip", "interp.hip", "texture.hip", "softras.hip",
-           "shade.hip", "optim.hip"]
+           "shade.hip", "optim.hip", "pbs.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

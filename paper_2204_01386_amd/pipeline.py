@@ -893,3 +893,128 @@ class FitLoop:
         st = self.st
         self.ts.run()
         self.adam_tex.step(st.ctx, st.g_tex, st._s())
+
+
+# ---------------------------------------------------------------------------
+# image-based physically-based shading
+# ---------------------------------------------------------------------------
+class PbsStep:
+    """Split-sum PBS lit by an environment map, on fixed geometry (the paper's
+    render graph in appendix B; appendix C optimises an environment map and
+    the roughness with it).  Parameters: the environment cube map, the albedo
+    texture and the material (metallic, roughness; device scalars).
+
+    Per step: the irradiance and prefiltered maps are filtered from the
+    environment (dense sums, exact adjoint), the albedo is sampled, the
+    lookup directions and per-level masks are formed, the maps are sampled,
+    the fragments shaded and blended, and the backward runs the reverse:
+    blend, shading (albedo, samples and material), the maps' texel
+    gradients by the inverse UV, the filters' adjoint to the environment,
+    and the albedo texture's gather from the cached inverse-UV map.  The
+    geometry-only nodes (rasterization, G-buffer, UVs, the albedo inverse
+    UV) are computed once by a TextureStep."""
+
+    def __init__(self, scene: Scene, env: np.ndarray, material=(0.5, 0.5), Si: int = 16, Sp: int = 32, L: int = 5,
+                 lut_n: int = 32, lut_m: int = 512, target: "PbsStep | None" = None, device="cuda",
+                 params: dict | None = None):
+        if scene.shading != "phong":
+            raise ValueError("PBS shading runs on a textured scene without normal or environment maps")
+        self.st = st = Step(scene, device, params=params)
+        self.dev = st.dev
+        f32 = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(st.dev)
+        self.env = f32(env)
+        self.S = self.env.shape[1]
+        self.Si, self.Sp, self.L = Si, Sp, L
+        self.material = f32(np.asarray(material, np.float32))
+        self.desc = Bd.IblDesc(self.S, Si, Sp, L)
+        e = lambda *s, dt=torch.float32: torch.empty(s, dtype=dt, device=st.dev)
+        N = st.B * st.K * st.H * st.W
+        self.N = N
+        self.irr, self.pref = e(6, Si, Si, 3), e(L, 6, Sp, Sp, 3)
+        self.norm = e(int(_lib.dressi_ibl_norm_bytes(C.byref(self.desc))) // 8, dt=torch.float64)
+        self.lut = e(lut_n, lut_n, 2)
+        st._chk(_lib.dressi_brdf_lut(st.ctx.handle, lut_n, lut_m, _p(self.lut), st._s()), "brdf_lut")
+        self.dir_n, self.dir_r = e(N, 3), e(N, 3)
+        self.ltid = e(L, N, dt=torch.int32)
+        self.irr_s, self.pref_s = e(N, 3), e(L, N, 3)
+        self.g_irr_s, self.g_pref_s = e(N, 3), e(L, N, 3)
+        self.g_irr, self.g_pref = e(6, Si, Si, 3), e(L, 6, Sp, Sp, 3)
+        self.g_env = torch.empty_like(self.env)
+        self.g_material = e(2)
+        self.cube_irr = Bd.TexDesc(Bd.TEX_CUBE, Si, Si, 3, Bd.WRAP_CLAMP, Bd.WRAP_CLAMP)
+        self.cube_pref = Bd.TexDesc(Bd.TEX_CUBE, Sp, Sp, 3, Bd.WRAP_CLAMP, Bd.WRAP_CLAMP)
+        self.ts = TextureStep(st)
+        if target is not None:
+            st.target.copy_(target.rgba())
+        Ct = st.Ct
+        self._pin = Bd.PbsIn()
+        pin = self._pin
+        pin.normal, pin.normal_stride = _cp(st.gbuf, 0), st.Cv
+        pin.pos, pin.pos_stride = _cp(st.gbuf, 3), st.Cv
+        pin.albedo, pin.albedo_stride = _cp(st.samp, 0), Ct
+        pin.irr, pin.irr_stride = _p(self.irr_s), 3
+        pin.pref, pin.pref_stride, pin.pref_level_stride = _p(self.pref_s), 3, N * 3
+        pin.material, pin.lut, pin.lut_n, pin.levels = _p(self.material), _p(self.lut), lut_n, L
+        self._pg = Bd.PbsGrad()
+        pg = self._pg
+        pg.albedo, pg.albedo_stride = _cp(st.g_samp, 0), Ct
+        pg.irr, pg.pref, pg.material = _p(self.g_irr_s), _p(self.g_pref_s), _p(self.g_material)
+
+    def _pref_level(self, t, l):
+        return C.c_void_p(t.data_ptr() + 4 * l * (t[0].numel()))
+
+    def forward(self):
+        st = self.st
+        h, s, ck = st.ctx.handle, st._s(), st._chk
+        B, K, H, W, L = st.B, st.K, st.H, st.W, self.L
+        S = B * K
+        ck(_lib.dressi_ibl_filter(h, _p(self.env), C.byref(self.desc), _p(self.irr), _p(self.pref), _p(self.norm),
+                                  s), "ibl_filter")
+        ck(_lib.dressi_texture(h, _p(st.tex), C.byref(st.desc), _p(st.uvbuf), _p(st.tri_id), S, H, W, _p(st.samp), s),
+           "texture")
+        ck(_lib.dressi_shade_pbs(h, C.byref(self._pin), _p(st.eye), _p(st.tri_id), B, K * H * W, None, _p(self.dir_n),
+                                 _p(self.dir_r), _p(self.ltid), s), "shade_pbs dirs")
+        ck(_lib.dressi_texture(h, _p(self.irr), C.byref(self.cube_irr), _p(self.dir_n), _p(st.tri_id), S, H, W,
+                               _p(self.irr_s), s), "texture irradiance")
+        for l in range(L):
+            ck(_lib.dressi_texture(h, self._pref_level(self.pref, l), C.byref(self.cube_pref), _p(self.dir_r),
+                                   self._pref_level(self.ltid, l), S, H, W, self._pref_level(self.pref_s, l), s),
+               "texture prefiltered")
+        ck(_lib.dressi_shade_pbs(h, C.byref(self._pin), _p(st.eye), _p(st.tri_id), B, K * H * W, _p(st.layer_color),
+                                 None, None, None, s), "shade_pbs")
+        ck(_lib.dressi_softras(h, _p(st.layer_color), _p(st.dist), _p(st.tri_id), B, K, H, W, 3, st.sigma, st.delta,
+                               st.blend, _p(st.color), _p(st.sil), _p(st.E), s), "softras")
+
+    def loss_and_grad(self):
+        self.st.loss_and_grad()
+
+    def backward(self):
+        st = self.st
+        h, s, ck = st.ctx.handle, st._s(), st._chk
+        B, K, H, W, L = st.B, st.K, st.H, st.W, self.L
+        S = B * K
+        ck(_lib.dressi_softras_bwd(h, _p(st.layer_color), _p(st.dist), _p(st.tri_id), B, K, H, W, 3, st.sigma,
+                                   _p(st.E), _p(st.g_color), _p(st.g_sil), _p(st.g_layer), None, s), "softras_bwd")
+        ck(_lib.dressi_shade_pbs_bwd(h, C.byref(self._pin), _p(st.eye), _p(st.tri_id), B, K * H * W, _p(st.g_layer),
+                                     None, None, C.byref(self._pg), s), "shade_pbs_bwd")
+        ck(_lib.dressi_texture_bwd(h, _p(self.irr), C.byref(self.cube_irr), _p(self.dir_n), _p(st.tri_id), S, H, W,
+                                   _p(self.g_irr_s), _p(self.g_irr), None, s), "texture_bwd irradiance")
+        for l in range(L):
+            ck(_lib.dressi_texture_bwd(h, self._pref_level(self.pref, l), C.byref(self.cube_pref), _p(self.dir_r),
+                                       self._pref_level(self.ltid, l), S, H, W, self._pref_level(self.g_pref_s, l),
+                                       self._pref_level(self.g_pref, l), None, s), "texture_bwd prefiltered")
+        ck(_lib.dressi_ibl_filter_bwd(h, C.byref(self.desc), _p(self.norm), _p(self.g_irr), _p(self.g_pref),
+                                      _p(self.g_env), s), "ibl_filter_bwd")
+        ck(_lib.dressi_texture_grad_invuv(h, C.byref(st.desc), _p(st.uvbuf), _p(st.tri_id), S, H, W, _p(self.ts.inv),
+                                          _p(st.g_samp), _p(st.g_tex), s), "texture_grad_invuv")
+
+    def run(self):
+        self.forward()
+        self.loss_and_grad()
+        self.backward()
+
+    def rgba(self):
+        return self.st.rgba()
+
+    def grads(self):
+        return {"env": self.g_env, "material": self.g_material, "tex": self.st.g_tex}

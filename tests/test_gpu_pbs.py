@@ -1,0 +1,151 @@
+"""Image-based PBS on the GPU against the oracle: the irradiance and GGX
+prefilter convolutions and their exact adjoint, the BRDF integration table,
+and split-sum shading forward and backward (lookup directions, per-level
+masks, every gradient including the material's scalars)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import pbs as OP
+from test_gpu_parity import assert_grad_close, assert_vals_close, dev, host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2204_01386_amd import binding
+    return binding
+
+
+@pytest.mark.parametrize("S,Si,Sp,L", [(16, 4, 8, 4), (12, 5, 3, 2)])
+def test_ibl_filter_and_adjoint(B, S, Si, Sp, L):
+    rng = np.random.default_rng(S + L)
+    env = rng.random((6, S, S, 3)).astype(np.float32)
+    irr, pref, norm = B.dressi_ibl_filter(dev(env), Si, Sp, L)
+    irr_o, pref_o = OP.ibl_filter(env, Si, Sp, L)
+    assert_vals_close(host(irr), irr_o, what="irradiance")
+    assert_vals_close(host(pref), pref_o, what="prefiltered")
+    gi = rng.standard_normal(irr_o.shape).astype(np.float32)
+    gp = rng.standard_normal(pref_o.shape).astype(np.float32)
+    ge = B.dressi_ibl_filter_bwd(S, norm, dev(gi), dev(gp))
+    assert_grad_close(host(ge), OP.ibl_filter_bwd(S, Si, Sp, L, gi, gp), what="environment gradient")
+
+
+def test_brdf_lut(B):
+    lut = B.dressi_brdf_lut(16, 128)
+    ref = OP.brdf_lut(16, 128)
+    assert np.abs(host(lut) - ref).max() < 1e-6
+
+
+def _frags(rng, Bv, Npv, L):
+    n = rng.standard_normal((Bv, Npv, 3))
+    n[..., 2] = np.abs(n[..., 2]) + 0.2
+    p = 0.4 * rng.standard_normal((Bv, Npv, 3))
+    eye = np.stack([[0.3, 0.5, 3.0], [-0.4, 0.2, 2.7]])[:Bv]
+    alb = rng.uniform(0.05, 0.95, (Bv, Npv, 3))
+    irr = rng.uniform(0.05, 1.0, (Bv, Npv, 3))
+    pref = rng.uniform(0.05, 1.0, (L, Bv, Npv, 3))
+    tid = rng.integers(-1, 40, (Bv, Npv)).astype(np.int32)
+    f32 = lambda a: np.ascontiguousarray(a, np.float32)
+    return f32(n), f32(p), f32(eye), f32(alb), f32(irr), f32(pref), tid
+
+
+@pytest.mark.parametrize("m,r", [(0.3, 0.37), (0.8, 0.9), (0.0, 1.0), (0.5, 0.0)])
+def test_shade_pbs_forward_and_backward(B, m, r):
+    rng = np.random.default_rng(int(100 * (m + r)))
+    Bv, Npv, L = 2, 700, 5
+    n, p, eye, alb, irr, pref, tid = _frags(rng, Bv, Npv, L)
+    lut = OP.brdf_lut(8, 256).astype(np.float32)
+    mat = np.array([m, r], np.float32)
+    N = Bv * Npv
+    t = {k: dev(v) for k, v in dict(n=n.reshape(N, 3), p=p.reshape(N, 3), a=alb.reshape(N, 3),
+                                     i=irr.reshape(N, 3), pr=pref.reshape(L, N, 3), m=mat, lut=lut,
+                                     eye=eye, tid=tid.reshape(N)).items()}
+    pin = B.pbs_in(t["n"], t["p"], t["m"], t["lut"], albedo=t["a"], irr=t["i"], pref=t["pr"])
+    ctx = B.context()
+    dir_n = torch.empty((N, 3), device="cuda")
+    dir_r = torch.empty((N, 3), device="cuda")
+    ltid = torch.empty((L, N), dtype=torch.int32, device="cuda")
+    col = torch.empty((N, 3), device="cuda")
+    P = lambda x: B._ptr(x)
+    ctx.check(B._lib.dressi_shade_pbs(ctx.handle, B.C.byref(pin), P(t["eye"]), P(t["tid"]), Bv, Npv, P(col),
+                                      P(dir_n), P(dir_r), P(ltid), B._stream()), "shade_pbs")
+    # oracle, one eye per fragment
+    eye_f = np.repeat(eye[:, None, :], Npv, 1)
+    g = rng.standard_normal((Bv, Npv, 3))
+    out_o, gr = OP.shade_and_grads(n, p, eye_f, alb, m, r, irr, pref, lut.astype(np.float64), L, tid, g)
+    cov = tid >= 0
+    assert_vals_close(host(col).reshape(Bv, Npv, 3), out_o, what="pbs colour")
+    assert np.abs(host(dir_n).reshape(Bv, Npv, 3)[cov] - gr["dir_n"][cov]).max() < 1e-6
+    assert np.abs(host(dir_r).reshape(Bv, Npv, 3)[cov] - gr["dir_r"][cov]).max() < 1e-6
+    l0 = min(int(np.floor(r * (L - 1))), L - 2)
+    want = np.where(cov[None], tid[None], -1).repeat(L, 0)
+    for l in range(L):
+        if l not in (l0, l0 + 1):
+            want[l] = -1
+    assert np.array_equal(host(ltid).reshape(L, Bv, Npv), want)
+    # backward, with direction gradients from the lookups
+    gdn = rng.standard_normal((N, 3)).astype(np.float32)
+    gdr = rng.standard_normal((L, N, 3)).astype(np.float32)
+    outs = {k: torch.empty((N, 3), device="cuda") for k in ("normal", "pos", "albedo", "irr")}
+    gpref = torch.empty((L, N, 3), device="cuda")
+    gmat = torch.empty(2, device="cuda")
+    pg = B.PbsGrad()
+    pg.normal, pg.normal_stride = P(outs["normal"]), 3
+    pg.pos, pg.pos_stride = P(outs["pos"]), 3
+    pg.albedo, pg.albedo_stride = P(outs["albedo"]), 3
+    pg.irr, pg.pref, pg.material = P(outs["irr"]), P(gpref), P(gmat)
+    # (device copies kept alive: a pointer of a temporary tensor could be
+    # handed to the next allocation before the kernel runs)
+    gd = dev(g.reshape(N, 3).astype(np.float32))
+    tgdn, tgdr = dev(gdn), dev(gdr)
+    ctx.check(B._lib.dressi_shade_pbs_bwd(ctx.handle, B.C.byref(pin), P(t["eye"]), P(t["tid"]), Bv, Npv, P(gd),
+                                          P(tgdn), P(tgdr), B.C.byref(pg), B._stream()), "shade_pbs_bwd")
+    # the oracle with the same float32 output gradient
+    _, gr = OP.shade_and_grads(n, p, eye_f, alb, m, r, irr, pref, lut.astype(np.float64), L, tid,
+                               g.astype(np.float32))
+    vn, vp = OP.dirs_vjp(n, p, eye_f, gdn.reshape(Bv, Npv, 3).astype(np.float64),
+                         gdr.sum(0).reshape(Bv, Npv, 3).astype(np.float64))
+    c3 = cov[..., None]
+    sh = lambda x: host(x).reshape(Bv, Npv, 3)
+    assert_grad_close(sh(outs["albedo"]), gr["albedo"], what="albedo")
+    assert_grad_close(sh(outs["irr"]), gr["irr_s"], what="irradiance sample")
+    assert_grad_close(host(gpref).reshape(L, Bv, Npv, 3), gr["pref_s"], what="prefiltered samples")
+    assert_grad_close(sh(outs["normal"]), gr["normal"] + np.where(c3, vn, 0.0), what="normal")
+    assert_grad_close(sh(outs["pos"]), gr["pos"] + np.where(c3, vp, 0.0), what="position")
+    gm = host(gmat).astype(np.float64)
+    for k, name in enumerate(("metallic", "roughness")):
+        ref = gr[name]
+        assert abs(gm[k] - ref) <= 1e-5 * max(abs(ref), 1e-3), (name, gm[k], ref)
+
+
+def test_pbs_step_matches_oracle(B):
+    """The whole PBS step on fixed geometry (2 views 64^2, HardSoftRas K = 2):
+    image, loss and the gradients of the environment map, the material and
+    the albedo texture against the oracle's step."""
+    from paper_2204_01386_amd import scenes
+    from paper_2204_01386_amd.pipeline import PbsStep
+    s = scenes.fit_scene(subdiv=3, H=64, n_views=2, tex_size=64)
+    env_t = scenes.cube_env_map(8, 5)
+    env0 = np.full_like(env_t, 0.5)
+    Si, Sp, L, N, M = 4, 8, 4, 16, 128
+    mat_t, mat0 = np.array([0.7, 0.3], np.float32), np.array([0.4, 0.6], np.float32)
+    tgt = PbsStep(s, env_t, mat_t, Si, Sp, L, N, M, params={"tex": torch.from_numpy(s.target_tex).cuda()})
+    tgt.forward()
+    ps = PbsStep(s, env0, mat0, Si, Sp, L, N, M, target=tgt)
+    ps.run()
+    torch.cuda.synchronize()
+    lut = OP.brdf_lut(N, M)
+    t_o = OP.pbs_forward(s, env_t, mat_t, s.target_tex, Si, Sp, L, lut)
+    f, g = OP.pbs_step(s, env0, mat0, s.tex, t_o["rgba"], Si, Sp, L, lut)
+    assert np.array_equal(host(ps.st.tri_id), f["tid"])
+    assert_vals_close(host(tgt.rgba()), t_o["rgba"], what="target image")
+    assert_vals_close(host(ps.rgba()), f["rgba"], what="image")
+    Lg = float(host(ps.st.loss)[0])
+    assert abs(Lg - g["loss"]) <= 1e-5 * g["loss"], (Lg, g["loss"])
+    assert_grad_close(host(ps.g_env), g["env"], what="environment gradient")
+    assert_grad_close(host(ps.st.g_tex), g["tex"], what="albedo texture gradient")
+    gm = host(ps.g_material).astype(np.float64)
+    assert np.abs(gm - g["material"]).max() <= 1e-4 * np.abs(g["material"]).max(), (gm, g["material"])
