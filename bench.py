@@ -607,6 +607,16 @@ def main():
                "surface_distance": [first["surface_distance"], last_sil["surface_distance"]],
                "color_l2": [t0["color_l2"], last["color_l2"]], "bin_overflow": fr["bin_overflow"]}
 
+    # ---- image-based PBS: the environment-map fit -------------------------
+    pbs = None
+    if args.fit and args.config == 2:
+        from paper_2204_01386_amd.fit import run_env_fit
+        er = run_env_fit()
+        c0, c1 = er["curve"][0], er["curve"][-1]
+        pbs = {"workload": er["workload"], "iterations": er["iterations"], "ms_per_iteration": er["ms_per_iteration"],
+               "loss": [c0["loss"], c1["loss"]], "env_rel_error": [c0["env_rel_error"], c1["env_rel_error"]],
+               "roughness": [c0["roughness"], c1["roughness"]], "roughness_target": er["material_target"][1]}
+
     # ---- CPU baseline: the oracle's step on the same workload --------------
     cpu = None
     if not args.no_cpu:
@@ -663,6 +673,7 @@ def main():
         "cpu_baseline": cpu,
         "paper_context": PAPER_CONTEXT,
         "fit": fit,
+        "pbs_env_fit": pbs,
         "multiview": multi,
         "uneven": uneven,
         "kernels": kernel_rows,
