@@ -129,7 +129,7 @@ def scene_for(cfg):
 FETCH_SCALE, WRITE_SCALE = 262144.0 / 131083.5, 1.0
 TRAFFIC = {
     "k_invuv_gather": {"src": "paper_2204_01386_amd/csrc/texture.hip",
-                       "sha": "bc91292cd3498bb52e427b69242e1fb08a67f7aa1dc642d48e410b752cccce48",
+                       "sha": "708ef0825b3942bf2313adc2f94413185a5c8f93046fa710e8ebea6cdabaa34f",
                        "fetch_kib": 10128.3125, "write_kib": 16384.0},
 }
 
