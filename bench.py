@@ -615,7 +615,8 @@ def main():
         c0, c1 = er["curve"][0], er["curve"][-1]
         pbs = {"workload": er["workload"], "iterations": er["iterations"], "ms_per_iteration": er["ms_per_iteration"],
                "loss": [c0["loss"], c1["loss"]], "env_rel_error": [c0["env_rel_error"], c1["env_rel_error"]],
-               "roughness": [c0["roughness"], c1["roughness"]], "roughness_target": er["material_target"][1]}
+               "roughness": [c0["roughness"], c1["roughness"]], "roughness_target": er["material_target"][1],
+               "kernels_ms": er["kernels"][:10]}
 
     # ---- CPU baseline: the oracle's step on the same workload --------------
     cpu = None

@@ -56,57 +56,58 @@ __device__ __forceinline__ double level_alpha(int l, int L) {
     return fmax(r * r, 1e-3);
 }
 
-// GGX weight of environment direction w for the lobe around R (n = v = R):
-// max(0, R.w) D(h), with (R.h)^2 = (1 + R.w) / 2 for unit vectors.
-__device__ __forceinline__ double ggx_weight(double rdw, double alpha) {
-    if (rdw <= 0.0) return 0.0;
-    const double a2 = alpha * alpha;
-    const double t = 0.5 * (1.0 + rdw) * (a2 - 1.0) + 1.0;
-    return rdw * a2 / (3.14159265358979323846 * t * t);
+// Every output of the filters: o < 6 Si^2 is an irradiance texel, the rest
+// the prefiltered levels, level by level.  (direction, alpha^2), alpha^2 < 0
+// marking the irradiance.
+__global__ void k_ibl_out_table(dressi_ibl_desc g, double4 *__restrict__ tab) {
+    const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t ni = 6ll * g.Si * g.Si, np = 6ll * g.Sp * g.Sp;
+    if (o >= ni + (int64_t)g.L * np) return;
+    double3 d;
+    double a2 = -1.0;
+    if (o < ni) {
+        d = cube_texel_dir(g.Si, o);
+    } else {
+        const int l = (int)((o - ni) / np);
+        d = cube_texel_dir(g.Sp, (o - ni) - (int64_t)l * np);
+        const double a = level_alpha(l, g.L);
+        a2 = a * a;
+    }
+    tab[o] = make_double4(d.x, d.y, d.z, a2);
 }
 
-// Output o of the filters: o < 6 Si^2 is an irradiance texel, the rest the
-// prefiltered levels, level by level.  Its direction and its kernel on
-// environment direction w.
-struct FilterOut {
-    double3 d;
-    int level;   // -1: irradiance
-};
-__device__ __forceinline__ FilterOut filter_out(const dressi_ibl_desc &g, int64_t o) {
-    FilterOut r;
-    const int64_t ni = 6ll * g.Si * g.Si, np = 6ll * g.Sp * g.Sp;
-    if (o < ni) {
-        r.level = -1;
-        r.d = cube_texel_dir(g.Si, o);
-    } else {
-        r.level = (int)((o - ni) / np);
-        r.d = cube_texel_dir(g.Sp, (o - ni) - (int64_t)r.level * np);
-    }
-    return r;
-}
-__device__ __forceinline__ double filter_kernel(const FilterOut &q, const dressi_ibl_desc &g, double3 w, double om) {
-    const double c = q.d.x * w.x + q.d.y * w.y + q.d.z * w.z;
-    const double k = q.level < 0 ? fmax(c, 0.0) : ggx_weight(c, level_alpha(q.level, g.L));
-    return k * om;
+// The filters' kernel between output q (direction, alpha^2) and environment
+// texel e (direction, solid angle): max(0, q.w) O for the irradiance; for a
+// prefiltered level max(0, R.w) D(h) O with (R.h)^2 = (1 + R.w) / 2 for unit
+// vectors, D(h) = alpha^2 / (pi t^2), t = (R.h)^2 (alpha^2 - 1) + 1 =
+// (1 - c) / 2 + (1 + c) alpha^2 / 2 (the form without cancellation: t is of
+// order alpha^2 near the lobe's axis).  c and t in double; the quotient in
+// float, where t's relative precision is kept.
+__device__ __forceinline__ float filter_kernel(const double4 &q, const double4 &e) {
+    const double c = q.x * e.x + q.y * e.y + q.z * e.z;
+    if (!(c > 0.0)) return 0.0f;
+    if (q.w < 0.0) return (float)(c * e.w);
+    const float t = (float)(0.5 * (1.0 - c) + 0.5 * (1.0 + c) * q.w);
+    return (float)(c * q.w * e.w) / (3.14159265358979f * t * t);
 }
 
 // one workgroup per output texel: out = sum_j env_j K_j / sum_j K_j
 __global__ void __launch_bounds__(PBS_BS)
-    k_ibl_filter(dressi_ibl_desc g, const double4 *__restrict__ tab, const float *__restrict__ env,
-                 float *__restrict__ irr, float *__restrict__ pref, double *__restrict__ norm) {
+    k_ibl_filter(dressi_ibl_desc g, const double4 *__restrict__ tab, const double4 *__restrict__ otab,
+                 const float *__restrict__ env, float *__restrict__ irr, float *__restrict__ pref,
+                 double *__restrict__ norm) {
     __shared__ double red[4][PBS_BS];
     const int64_t o = blockIdx.x;
-    const FilterOut q = filter_out(g, o);
+    const double4 q = otab[o];
     const int64_t ne = 6ll * g.S * g.S;
     double s0 = 0.0, s1 = 0.0, s2 = 0.0, sw = 0.0;
     for (int64_t j = threadIdx.x; j < ne; j += PBS_BS) {
-        const double4 t = tab[j];
-        const double k = filter_kernel(q, g, make_double3(t.x, t.y, t.z), t.w);
-        if (k == 0.0) continue;
-        s0 += k * env[3 * j];
-        s1 += k * env[3 * j + 1];
-        s2 += k * env[3 * j + 2];
-        sw += k;
+        const float k = filter_kernel(q, tab[j]);
+        if (k == 0.0f) continue;
+        s0 += (double)(k * env[3 * j]);
+        s1 += (double)(k * env[3 * j + 1]);
+        s2 += (double)(k * env[3 * j + 2]);
+        sw += (double)k;
     }
     red[0][threadIdx.x] = s0;
     red[1][threadIdx.x] = s1;
@@ -128,26 +129,33 @@ __global__ void __launch_bounds__(PBS_BS)
     norm[o] = red[3][0];
 }
 
-// one workgroup per environment texel j: g_env_j = sum_o g_o K_oj / norm_o
+// every output's gradient over its denominator, g_o / norm_o
+__global__ void k_ibl_bwd_scale(dressi_ibl_desc g, const double *__restrict__ norm, const float *__restrict__ g_irr,
+                                const float *__restrict__ g_pref, float4 *__restrict__ gs) {
+    const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t ni = 6ll * g.Si * g.Si, no = ni + (int64_t)g.L * 6 * g.Sp * g.Sp;
+    if (o >= no) return;
+    const float *go = o < ni ? g_irr + 3 * o : g_pref + 3 * (o - ni);
+    const double inv = 1.0 / norm[o];
+    gs[o] = make_float4((float)(go[0] * inv), (float)(go[1] * inv), (float)(go[2] * inv), 0.0f);
+}
+
+// one workgroup per environment texel j: g_env_j = sum_o K_oj g_o / norm_o
 __global__ void __launch_bounds__(PBS_BS)
-    k_ibl_filter_bwd(dressi_ibl_desc g, const double4 *__restrict__ tab, const double *__restrict__ norm,
-                     const float *__restrict__ g_irr, const float *__restrict__ g_pref,
-                     float *__restrict__ g_env) {
+    k_ibl_filter_bwd(dressi_ibl_desc g, const double4 *__restrict__ tab, const double4 *__restrict__ otab,
+                     const float4 *__restrict__ gs, float *__restrict__ g_env) {
     __shared__ double red[3][PBS_BS];
     const int64_t j = blockIdx.x;
-    const double4 t = tab[j];
-    const double3 w = make_double3(t.x, t.y, t.z);
-    const int64_t ni = 6ll * g.Si * g.Si, no = ni + (int64_t)g.L * 6 * g.Sp * g.Sp;
+    const double4 e = tab[j];
+    const int64_t no = 6ll * g.Si * g.Si + (int64_t)g.L * 6 * g.Sp * g.Sp;
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
     for (int64_t o = threadIdx.x; o < no; o += PBS_BS) {
-        const FilterOut q = filter_out(g, o);
-        const double k = filter_kernel(q, g, w, t.w);
-        if (k == 0.0) continue;
-        const float *go = o < ni ? g_irr + 3 * o : g_pref + 3 * (o - ni);
-        const double kk = k / norm[o];
-        s0 += kk * go[0];
-        s1 += kk * go[1];
-        s2 += kk * go[2];
+        const float k = filter_kernel(otab[o], e);
+        if (k == 0.0f) continue;
+        const float4 q = gs[o];
+        s0 += (double)(k * q.x);
+        s1 += (double)(k * q.y);
+        s2 += (double)(k * q.z);
     }
     red[0][threadIdx.x] = s0;
     red[1][threadIdx.x] = s1;
@@ -172,6 +180,25 @@ static int check_ibl(dressi_ctx *ctx, const dressi_ibl_desc *d) {
     return DRESSI_OK;
 }
 
+// The environment texels' and the outputs' tables, in the context's scratch.
+// (with gs, room for the backward's per-output gradient scale as well)
+static int ibl_tables(dressi_ctx *ctx, const dressi_ibl_desc *d, hipStream_t st, double4 *&tab, double4 *&otab,
+                      float4 **gs = nullptr) {
+    const int64_t ne = 6ll * d->S * d->S;
+    const int64_t no = 6ll * d->Si * d->Si + (int64_t)d->L * 6 * d->Sp * d->Sp;
+    Carver c;
+    const size_t o_t = c.take(sizeof(double4) * (size_t)ne), o_o = c.take(sizeof(double4) * (size_t)no);
+    const size_t o_g = c.take(sizeof(float4) * (size_t)no);
+    int rc = dressi_scratch(ctx, c.off, st);
+    if (rc) return rc;
+    tab = at<double4>(ctx->scratch, o_t);
+    otab = at<double4>(ctx->scratch, o_o);
+    if (gs) *gs = at<float4>(ctx->scratch, o_g);
+    DR_LAUNCH("k_cube_table", (k_cube_table), (int)((ne + 255) / 256), 256, 0, st, d->S, tab);
+    DR_LAUNCH("k_ibl_out_table", (k_ibl_out_table), (int)((no + 255) / 256), 256, 0, st, *d, otab);
+    return DRESSI_OK;
+}
+
 extern "C" size_t dressi_ibl_norm_bytes(const dressi_ibl_desc *d) {
     if (!d || d->Si < 1 || d->Sp < 1 || d->L < 2) return 0;
     return sizeof(double) * (6ull * d->Si * d->Si + (size_t)d->L * 6ull * d->Sp * d->Sp);
@@ -183,12 +210,10 @@ extern "C" int dressi_ibl_filter(dressi_ctx *ctx, const float *env, const dressi
     if (rc) return rc;
     if (!env || !irr || !pref || !norm) return dressi_fail(ctx, DRESSI_EINVAL, "ibl_filter: null pointer");
     hipStream_t st = (hipStream_t)stream;
-    const int64_t ne = 6ll * d->S * d->S;
-    if ((rc = dressi_scratch(ctx, sizeof(double4) * (size_t)ne, st))) return rc;
-    double4 *tab = at<double4>(ctx->scratch, 0);
-    DR_LAUNCH("k_cube_table", (k_cube_table), (int)((ne + 255) / 256), 256, 0, st, d->S, tab);
+    double4 *tab, *otab;
+    if ((rc = ibl_tables(ctx, d, st, tab, otab))) return rc;
     const int64_t no = 6ll * d->Si * d->Si + (int64_t)d->L * 6 * d->Sp * d->Sp;
-    DR_LAUNCH("k_ibl_filter", (k_ibl_filter), (int)no, PBS_BS, 0, st, *d, tab, env, irr, pref, norm);
+    DR_LAUNCH("k_ibl_filter", (k_ibl_filter), (int)no, PBS_BS, 0, st, *d, tab, otab, env, irr, pref, norm);
     return dressi_launch_check(ctx, "ibl_filter");
 }
 
@@ -200,12 +225,14 @@ extern "C" int dressi_ibl_filter_bwd(dressi_ctx *ctx, const dressi_ibl_desc *d, 
     if (!norm || !grad_irr || !grad_pref || !grad_env)
         return dressi_fail(ctx, DRESSI_EINVAL, "ibl_filter_bwd: null pointer");
     hipStream_t st = (hipStream_t)stream;
+    double4 *tab, *otab;
+    float4 *gs;
+    if ((rc = ibl_tables(ctx, d, st, tab, otab, &gs))) return rc;
     const int64_t ne = 6ll * d->S * d->S;
-    if ((rc = dressi_scratch(ctx, sizeof(double4) * (size_t)ne, st))) return rc;
-    double4 *tab = at<double4>(ctx->scratch, 0);
-    DR_LAUNCH("k_cube_table", (k_cube_table), (int)((ne + 255) / 256), 256, 0, st, d->S, tab);
-    DR_LAUNCH("k_ibl_filter_bwd", (k_ibl_filter_bwd), (int)ne, PBS_BS, 0, st, *d, tab, norm, grad_irr, grad_pref,
-              grad_env);
+    const int64_t no = 6ll * d->Si * d->Si + (int64_t)d->L * 6 * d->Sp * d->Sp;
+    DR_LAUNCH("k_ibl_bwd_scale", (k_ibl_bwd_scale), (int)((no + 255) / 256), 256, 0, st, *d, norm, grad_irr,
+              grad_pref, gs);
+    DR_LAUNCH("k_ibl_filter_bwd", (k_ibl_filter_bwd), (int)ne, PBS_BS, 0, st, *d, tab, otab, gs, grad_env);
     return dressi_launch_check(ctx, "ibl_filter_bwd");
 }
 

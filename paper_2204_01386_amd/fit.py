@@ -210,6 +210,7 @@ def run_env_fit(n_iter: int = 300, every: int = 50, S: int = 32, Si: int = 8, Sp
     saved = [t.clone() for t in (ps.env, ps.material, adam_env.m, adam_env.v, adam_env.state, adam_r.m, adam_r.v,
                                  adam_r.state)]
     ms = _time(g, time_reps)
+    kernels = _profile(iteration)
     for dst, src in zip((ps.env, ps.material, adam_env.m, adam_env.v, adam_env.state, adam_r.m, adam_r.v,
                          adam_r.state), saved):
         dst.copy_(src)
@@ -217,4 +218,25 @@ def run_env_fit(n_iter: int = 300, every: int = 50, S: int = 32, Si: int = 8, Sp
     return {"workload": f"metallic pear ({st.T} triangles), {n_views} views {H}x{H}, HardSoftRas K={st.K}, "
                         f"env 6x{S}^2, irradiance 6x{Si}^2, prefiltered {L}x6x{Sp}^2",
             "material_target": list(material_t), "roughness_start": rough0, "iterations": n_iter,
-            "ms_per_iteration": round(ms, 4), "curve": curve}
+            "ms_per_iteration": round(ms, 4), "kernels": kernels, "curve": curve}
+
+
+def _profile(fn, cap: int = 4096) -> list:
+    """Per-kernel time of one eager call of fn (the library's event profiler:
+    each launch timed from its own dispatch), largest first."""
+    import ctypes as C
+
+    from . import binding as Bd
+    torch.cuda.synchronize()
+    Bd._lib.dressi_profile_start(cap)
+    fn()
+    torch.cuda.synchronize()
+    names = (C.c_char_p * cap)()
+    ms = (C.c_float * cap)()
+    n = Bd._lib.dressi_profile_read(names, ms, cap)
+    Bd._lib.dressi_profile_start(0)
+    tot = {}
+    for i in range(max(n, 0)):
+        k = names[i].decode()
+        tot[k] = tot.get(k, 0.0) + ms[i]
+    return [[k, round(v, 4)] for k, v in sorted(tot.items(), key=lambda kv: -kv[1])]
