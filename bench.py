@@ -448,6 +448,7 @@ def measure_batch(scene_list, steps, warmup, prof_steps):
     if ctx.check_status() != 0:
         raise SystemExit("tile-bin capacity overflow in the timed region")
     del graph
+    ms_tex = texture_only_ms(bs, steps, warmup)
     # plain: one standalone step per view, eager
     plain = [Step(sc, target=make_target(sc)) for sc in scene_list]
     for ps in plain:
@@ -483,6 +484,7 @@ def measure_batch(scene_list, steps, warmup, prof_steps):
         per[k] = per.get(k, 0.0) + ms[i]
     table = sorted(((k, v / max(prof_steps, 1)) for k, v in per.items()), key=lambda x: -x[1])
     return {"ms_per_step": ms_batched, "plain_ms_per_step": ms_plain, "step_alg_bytes": step_bytes,
+            "texture_only_ms_per_step": ms_tex,
             "table": table, "T": bs.T, "pixels": int(sum(s.H * s.W for s in scene_list)),
             "canvas": (bs.W, bs.H), "tuned": tuned}
 
@@ -500,6 +502,7 @@ def uneven_line(steps, prof_steps):
             "tris_per_s": round(m["T"] / (m["ms_per_step"] * 1e-3), 1),
             "plain_ms_per_step": round(m["plain_ms_per_step"], 4),
             "batched_vs_plain_speedup": round(m["plain_ms_per_step"] / m["ms_per_step"], 3),
+            "texture_only_ms_per_step": round(m["texture_only_ms_per_step"], 4),
             "step_alg_bytes": m["step_alg_bytes"],
             "step_hbm_frac": round(m["step_alg_bytes"] / (m["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
             "autotune": _tuned_json(m["tuned"]),

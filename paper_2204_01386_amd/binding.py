@@ -30,7 +30,8 @@ TUNE_BIN_CAPACITY, TUNE_HARD_RASTER, TUNE_HYBRID_WEIGHT = 1, 2, 3
 WRAP_REPEAT, WRAP_CLAMP = 0, 1
 BLEND_HSR, BLEND_AA, BLEND_SOFTRAS, BLEND_HARD = 0, 1, 2, 3
 
-STATUS = {0: "ok", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "EOVERFLOW"}
+OK, EINVAL, ENOMEM, EHIP, EOVERFLOW = 0, -1, -2, -3, -4
+STATUS = {OK: "ok", EINVAL: "EINVAL", ENOMEM: "ENOMEM", EHIP: "EHIP", EOVERFLOW: "EOVERFLOW"}
 
 
 class TexDesc(C.Structure):

@@ -403,7 +403,7 @@ class TextureStep:
     and texture gradients are bitwise those of the full step with the same
     parameters; refresh() recomputes the cache after the geometry changed."""
 
-    def __init__(self, step: Step):
+    def __init__(self, step: "Step | BatchStep"):
         if step.tex is None:
             raise ValueError("a texture-only step needs a textured scene")
         self.st = step
@@ -532,6 +532,14 @@ class BatchStep(_TwoStreams):
     Phong, one 2-D texture each): the meshes are concatenated, every view is
     drawn into its own rectangle of one image and every stage is one launch
     for the whole batch.  The loss is the sum of the per-view L2 means."""
+
+    # the whole batch is one slice of one layer, shaded with Phong and a hard
+    # blend (the attributes a TextureStep reads from the step it wraps)
+    B = K = 1
+    mode = Bd.SHADE_PHONG
+    blend = Bd.BLEND_HARD
+    sigma, delta = 1.0, 0.0
+    env = dist = g_dir = None
 
     def __init__(self, scenes_list, device="cuda", target: "BatchStep | None" = None,
                  params: list | None = None):
@@ -725,6 +733,10 @@ class BatchStep(_TwoStreams):
         """tri_id of view i in its own triangle numbering (-1 = empty)."""
         t = self.tri_id[0, 0][self.view_rect(i)]
         return torch.where(t >= 0, t - int(self.tbase[i]), t)
+
+    def grads(self):
+        """Gradients of the loss w.r.t. the batch's positions and textures [n,Ht,Wt,Ct]."""
+        return {"pos": self.g_pos, "tex": self.g_tex}
 
     def view_grads(self, i):
         return {"pos": self.g_pos[int(self.vbase[i]):int(self.vbase[i + 1])], "tex": self.g_tex[i]}

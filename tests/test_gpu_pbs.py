@@ -149,3 +149,44 @@ def test_pbs_step_matches_oracle(B):
     assert_grad_close(host(ps.st.g_tex), g["tex"], what="albedo texture gradient")
     gm = host(ps.g_material).astype(np.float64)
     assert np.abs(gm - g["material"]).max() <= 1e-4 * np.abs(g["material"]).max(), (gm, g["material"])
+
+
+def test_new_entry_points_empty_and_rejected(B):
+    """Empty inputs do nothing (or write the empty sum); bad arguments are
+    rejected before any launch."""
+    ctx = B.context()
+    P, S = B._ptr, B._stream()
+    # the Laplacian of an empty mesh: value 0
+    val = torch.full((1,), 7.0, device="cuda")
+    ctx.check(B._lib.dressi_laplacian_reg(ctx.handle, None, None, 0, 0, None, 1.0, 1.0, None, None, None, P(val),
+                                          S), "empty laplacian")
+    torch.cuda.synchronize()
+    assert float(val.item()) == 0.0
+    # shading of no fragment: nothing written, the material gradient is 0
+    pin = B.PbsIn()
+    pin.levels = 2
+    pg = B.PbsGrad()
+    gm = torch.full((2,), 3.0, device="cuda")
+    pg.material = P(gm)
+    assert B._lib.dressi_shade_pbs(ctx.handle, B.C.byref(pin), None, None, 0, 0, None, None, None, None, S) == 0
+    assert B._lib.dressi_shade_pbs_bwd(ctx.handle, B.C.byref(pin), None, None, 0, 0, None, None, None,
+                                       B.C.byref(pg), S) == 0
+    torch.cuda.synchronize()
+    assert (gm == 0).all()
+    # an inverse-UV map of zero slices
+    tex = torch.zeros((8, 8, 4), device="cuda")
+    inv = B.dressi_invuv_build(tex, torch.zeros((0, 4, 4, 2), device="cuda"),
+                               torch.zeros((1, 4, 4), dtype=torch.int32, device="cuda"))
+    assert inv.numel() == 0
+    # rejected descriptors and sizes
+    bad = B.IblDesc(8, 4, 4, 1)   # L < 2
+    e = torch.zeros((6, 8, 8, 3), device="cuda")
+    assert B._lib.dressi_ibl_filter(ctx.handle, P(e), B.C.byref(bad), P(e), P(e), P(e), S) == B.EINVAL
+    assert B._lib.dressi_brdf_lut(ctx.handle, 0, 16, P(e), S) == B.EINVAL
+    pin.levels = 1
+    pin.normal, pin.normal_stride, pin.pos, pin.pos_stride, pin.material = P(e), 3, P(e), 3, P(e)
+    assert B._lib.dressi_shade_pbs(ctx.handle, B.C.byref(pin), P(e), P(e), 1, 4, None, P(e), None, None,
+                                   S) == B.EINVAL
+    mis = torch.zeros(4, dtype=torch.int32, device="cuda")[1:]   # a state not 16-byte aligned
+    p = torch.zeros(4, device="cuda")
+    assert B._lib.dressi_adam(ctx.handle, P(p), P(p), P(p), P(p), 4, 0.01, 0.9, 0.999, 1e-8, P(mis), S) == B.EINVAL

@@ -156,3 +156,27 @@ def test_texture_step_graph_replay(B, concurrent):
         g.replay()
         torch.cuda.synchronize()
         _assert_same(ref, _texture_state(st), f"replay {rep}")
+
+
+def test_texture_step_uneven_batch(B):
+    """Texture-only steps of an uneven batch (texture array, one layer per
+    instance): bitwise the full batched step's image, loss and texture
+    gradients, before and after a texture update."""
+    from paper_2204_01386_amd.pipeline import BatchStep, TextureStep, make_batch_target
+    sl = scenes.config4(seed=3, n=5, t_min=200, t_max=2e4, sizes=(128, 256), tex_size=64)
+    bs = BatchStep(sl, target=make_batch_target(sl))
+    bs.run()
+    torch.cuda.synchronize()
+    full = _texture_state(bs)
+    ts = TextureStep(bs)
+    ts.run()
+    torch.cuda.synchronize()
+    _assert_same(full, _texture_state(bs), "uneven texture-only step")
+    with torch.no_grad():
+        bs.tex.sub_(0.5 * bs.g_tex)
+    bs.run()
+    torch.cuda.synchronize()
+    full2 = _texture_state(bs)
+    ts.run()
+    torch.cuda.synchronize()
+    _assert_same(full2, _texture_state(bs), "uneven texture-only step after an update")
