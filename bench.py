@@ -59,6 +59,8 @@ def parse():
     ap.add_argument("--no-uneven", dest="uneven", action="store_false",
                     help="skip the 64-instance uneven batch measurement")
     ap.add_argument("--uneven-steps", type=int, default=20)
+    ap.add_argument("--fits-only", action="store_true",
+                    help="only the two-stage fit and the environment-map fit (one JSON line)")
     ap.add_argument("--kr-sweep", action="store_true",
                     help="only the K x r sweep of the sphere-to-pear silhouette fit (one JSON line)")
     ap.add_argument("--no-fit", dest="fit", action="store_false",
@@ -535,6 +537,15 @@ def main():
     if args.paper_table:
         print(json.dumps({"paper_table": paper_table(min(args.steps, 50), min(args.warmup, 5)),
                           "note": "white Lambert spheres here, silhouette shading in the paper; context only"}))
+        return
+    if args.fits_only:
+        from paper_2204_01386_amd import scenes as _sc
+        from paper_2204_01386_amd.fit import run_env_fit, run_fit
+        fr = run_fit(_sc.fit_scene())
+        er = run_env_fit()
+        print(json.dumps({"fit": {k: fr[k] for k in ("workload", "ms_per_iteration", "iterations")},
+                          "pbs_env_fit": {k: er[k] for k in ("workload", "ms_per_iteration", "iterations",
+                                                             "kernels")}}))
         return
     if args.kr_sweep:
         from paper_2204_01386_amd.fit import kr_sweep
