@@ -131,7 +131,7 @@ def scene_for(cfg):
 FETCH_SCALE, WRITE_SCALE = 262144.0 / 131083.5, 1.0
 TRAFFIC = {
     "k_invuv_gather": {"src": "paper_2204_01386_amd/csrc/texture.hip",
-                       "sha": "708ef0825b3942bf2313adc2f94413185a5c8f93046fa710e8ebea6cdabaa34f",
+                       "sha": "cb40e8264c0b66a037f82fecc78b5df5aa2727ec99bf94e05873883dfaa1c204",
                        "fetch_kib": 10128.3125, "write_kib": 16384.0},
 }
 
