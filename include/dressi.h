@@ -486,7 +486,7 @@ typedef struct {
  *   n' = normalize(n), v = normalize(eye - p), c = max(n'.v, 1e-4),
  *   dir_n = n', dir_r = R = 2 (n'.v) n' - v,
  *   F0 = 0.04 (1 - m) + a m,  F = F0 + (max(1 - r, F0) - F0)(1 - c)^5,
- *   x = r (L-1), l0 = min(floor x, L-2), f = x - l0,
+ *   x = clamp(r, 0, 1) (L-1), l0 = min(floor x, L-2), f = x - l0,
  *   P = (1 - f) pref_l0 + f pref_l0+1,  (A, B) = lut bilinear (clamped) at (c, r),
  *   C = (1 - F)(1 - m) a irr + P (F0 A + B),  color = C / (1 + C).
  * Writes, when non-NULL: dir_n, dir_r [N,3] and level_tri_id [L,N] (tri_id

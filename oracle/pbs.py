@@ -36,7 +36,7 @@ definitions.  The readings taken here:
   albedo a (rgb), metallic m and roughness r (scalars of the material):
       v = normalize(eye - p),  c = max(n'.v, 1e-4),  R = 2 (n'.v) n' - v,
       F0 = 0.04 (1 - m) + a m,  F = F0 + (max(1 - r, F0) - F0)(1 - c)^5,
-      x = r (L - 1), l0 = min(floor(x), L - 2), f = x - l0,
+      x = clamp(r, 0, 1) (L - 1), l0 = min(floor(x), L - 2), f = x - l0,
       P = (1 - f) pref_l0(R) + f pref_l0+1(R)   (bilinear cube lookups),
       (A, B) = the table sampled bilinearly (clamped) at (c, r),
       C = (1 - F)(1 - m) a irr(n') + P (F0 A + B),   out = C / (1 + C).
@@ -214,7 +214,7 @@ def pbs_shade(n, p, eye, albedo, metallic, roughness, irr_s, pref_s, lut, L):
     F0 = 0.04 * (1.0 - metallic) + albedo * metallic
     w5 = ((1.0 - c) ** 5)[..., None]
     F = F0 + (torch.maximum(1.0 - roughness, F0) - F0) * w5
-    x = roughness * (L - 1)
+    x = torch.clamp(roughness, 0.0, 1.0) * (L - 1)
     l0 = int(min(math.floor(float(x.detach())), L - 2))
     f = x - l0
     P = (1.0 - f) * pref_s[l0] + f * pref_s[l0 + 1]
@@ -284,7 +284,7 @@ def pbs_forward(scene, env, material, tex, Si, Sp, L, lut):
     dn = np.where(cov[..., None], nn.numpy(), 0.0).astype(np.float32)
     dr = np.where(cov[..., None], R.numpy(), 0.0).astype(np.float32)
     m, r = float(material[0]), float(material[1])
-    l0 = min(int(math.floor(r * (L - 1))), L - 2)
+    l0 = min(int(math.floor(min(max(r, 0.0), 1.0) * (L - 1))), L - 2)
     tid_l = [np.where(cov, tid, -1) if l in (l0, l0 + 1) else np.full_like(tid, -1) for l in range(L)]
     irr_s = cube_sample(irr, dn, tid)
     pref_s = np.stack([cube_sample(pref[l], dr, tid_l[l]) for l in range(L)])

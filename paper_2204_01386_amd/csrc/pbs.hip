@@ -285,6 +285,7 @@ struct PbsFrag {
     double nlen, vlen, ndv, c;
     int l0;
     double f;
+    bool rin;   // roughness inside [0, 1]: the level weight depends on it
 };
 
 __device__ __forceinline__ PbsFrag pbs_geometry(const dressi_pbs_in &in, const float *eye, int64_t i,
@@ -299,9 +300,12 @@ __device__ __forceinline__ PbsFrag pbs_geometry(const dressi_pbs_in &in, const f
     q.ndv = q.nn.x * q.v.x + q.nn.y * q.v.y + q.nn.z * q.v.z;
     q.c = fmax(q.ndv, 1e-4);
     q.R = make_double3(2.0 * q.ndv * q.nn.x - q.v.x, 2.0 * q.ndv * q.nn.y - q.v.y, 2.0 * q.ndv * q.nn.z - q.v.z);
-    const double x = rough * (in.levels - 1);
+    // the level pair follows the roughness clamped to [0, 1] (also keeping
+    // the level index in range for any roughness, NaN included)
+    const double x = fmin(fmax(rough, 0.0), 1.0) * (in.levels - 1);
     q.l0 = min((int)floor(x), in.levels - 2);
     q.f = x - q.l0;
+    q.rin = rough >= 0.0 && rough <= 1.0;
     return q;
 }
 
@@ -460,7 +464,7 @@ __global__ void __launch_bounds__(PBS_BS)
                         g.pref[(int64_t)l * 3 * n + 3 * i + ch] =
                             l == q.l0 ? (float)(gP * (1.0 - q.f)) : (l == q.l0 + 1 ? (float)(gP * q.f) : 0.0f);
             }
-            gr += gf * (L - 1);
+            if (q.rin) gr += gf * (L - 1);
             double gc = gw5 * (-5.0 * pow(1.0 - q.c, 4.0)) + gA * ab.dAc + gB * ab.dBc;
             gr += gA * ab.dAr + gB * ab.dBr;
             if (g.normal || g.pos) {

@@ -52,7 +52,7 @@ def _frags(rng, Bv, Npv, L):
     return f32(n), f32(p), f32(eye), f32(alb), f32(irr), f32(pref), tid
 
 
-@pytest.mark.parametrize("m,r", [(0.3, 0.37), (0.8, 0.9), (0.0, 1.0), (0.5, 0.0)])
+@pytest.mark.parametrize("m,r", [(0.3, 0.37), (0.8, 0.9), (0.0, 1.0), (0.5, 0.0), (0.4, -0.2), (0.4, 1.3)])
 def test_shade_pbs_forward_and_backward(B, m, r):
     rng = np.random.default_rng(int(100 * (m + r)))
     Bv, Npv, L = 2, 700, 5
@@ -80,7 +80,7 @@ def test_shade_pbs_forward_and_backward(B, m, r):
     assert_vals_close(host(col).reshape(Bv, Npv, 3), out_o, what="pbs colour")
     assert np.abs(host(dir_n).reshape(Bv, Npv, 3)[cov] - gr["dir_n"][cov]).max() < 1e-6
     assert np.abs(host(dir_r).reshape(Bv, Npv, 3)[cov] - gr["dir_r"][cov]).max() < 1e-6
-    l0 = min(int(np.floor(r * (L - 1))), L - 2)
+    l0 = min(int(np.floor(min(max(r, 0.0), 1.0) * (L - 1))), L - 2)
     want = np.where(cov[None], tid[None], -1).repeat(L, 0)
     for l in range(L):
         if l not in (l0, l0 + 1):
