@@ -84,6 +84,10 @@ int dressi_reserve(dressi_ctx *ctx, size_t bytes, int64_t bin_entries);
  * graph capture).  Pass the largest shapes of the step. */
 size_t dressi_scratch_bytes(int B, int V, int T, int H, int W, int K, float r,
                             int Va, int C, int64_t tex_cells, int tex_slices);
+/* (The entry points declared after the rendering stages, the inverse-UV
+ * split, the optimisation loop and image-based PBS, are not covered by this
+ * estimate: one eager call of each with the step's shapes sizes the scratch
+ * before a capture, or a capture without it fails with DRESSI_ENOMEM.) */
 /* Waits for `stream`, then returns DRESSI_EOVERFLOW (and clears the flag) if a
  * rasterization since the last check overflowed the bin capacity; *needed
  * receives the capacity that call required (may be NULL). */
