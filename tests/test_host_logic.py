@@ -75,3 +75,29 @@ def test_paper_table_scene_shapes():
         assert abs(sc.tris.shape[0] - T) / T < 0.02
         assert sc.mvp.shape == (6, 4, 4) and sc.shading == "lambert" and sc.K == 1
         assert np.all(sc.color == 1.0) and sc.tris.max() < sc.pos.shape[0]
+
+
+def test_fit_scene_and_surface_distance():
+    """The fit scene: a sphere and a pear of one topology, both closed and
+    outward-facing; the surface-distance metric is 0 on the surface itself,
+    equals an offset of a sphere, and the start lies off the target."""
+    from paper_2204_01386_amd.fit import mean_surface_distance, surface_samples
+    from scipy.spatial import cKDTree
+    s = scenes.fit_scene(subdiv=3)
+    assert s.pos.shape == s.target_pos.shape and s.tris.max() < s.pos.shape[0]
+    assert s.K == 2 and abs(s.r - 0.01) < 1e-12 and s.extra["blend"] == "hsr" and s.mvp.shape[0] == 6
+    # every edge shared by exactly two triangles (closed), outward normals
+    e = np.sort(np.concatenate([s.tris[:, [0, 1]], s.tris[:, [1, 2]], s.tris[:, [2, 0]]]), 1)
+    _, cnt = np.unique(e, axis=0, return_counts=True)
+    assert (cnt == 2).all()
+    for p in (s.pos, s.target_pos):
+        fn = np.cross(p[s.tris[:, 1]] - p[s.tris[:, 0]], p[s.tris[:, 2]] - p[s.tris[:, 0]])
+        assert (fn * p[s.tris].mean(1)).sum() > 0
+    tree = cKDTree(surface_samples(s.target_pos, s.tris))
+    assert mean_surface_distance(s.target_pos, tree) == 0.0
+    assert mean_surface_distance(s.pos, tree) > 0.02
+    # a unit sphere's samples against points at radius 1.5: distance 0.5 (up to the sampling)
+    p, tris = scenes.icosphere(3)
+    tree = cKDTree(surface_samples(p, tris, n=8))
+    d = mean_surface_distance(1.5 * p, tree)
+    assert abs(d - 0.5) < 2e-3
