@@ -117,15 +117,17 @@ def run_fit(scene: Scene, n_sil: int = 300, n_tex: int = 200, every: int = 25, l
             "curve": curve}
 
 
-def kr_sweep(Ks=(1, 2, 3, 4, 5), r_px=(1, 2, 3, 5, 7), checkpoints=(50, 300), seed: int = 0,
-             blend: str = "hsr") -> dict:
+def kr_sweep(Ks=(1, 2, 3, 4, 5), r_px=(1, 2, 3, 5, 7), checkpoints=(500, 2500), seed: int = 0,
+             blend: str = "hsr", lap_gamma: float = 0.999) -> dict:
     """The paper's validation of HardSoftRas settings (§4.2: a heatmap over K
     and r of the fitted geometry's distance to the target, early and late in
     the optimisation) on the sphere-to-pear silhouette fit: for every (K, r)
     the target is rendered with the same setting, and the mean distance of
     the fitted vertices to the target surface is recorded at each checkpoint
-    (iterations of the silhouette stage)."""
-    out = {"checkpoints": list(checkpoints), "K": list(Ks), "r_px": list(r_px), "blend": blend,
+    (iterations of the silhouette stage).  The regulariser decays by
+    lap_gamma per iteration (0.999: to a tenth over the 2,500 iterations;
+    a schedule that reaches zero lets the silhouette-only fit drift)."""
+    out = {"checkpoints": list(checkpoints), "K": list(Ks), "r_px": list(r_px), "blend": blend, "lap_gamma": lap_gamma,
            "surface_distance": {}, "ms_per_iteration": {}}
     base = None
     for K in Ks:
@@ -135,7 +137,7 @@ def kr_sweep(Ks=(1, 2, 3, 4, 5), r_px=(1, 2, 3, 5, 7), checkpoints=(50, 300), se
             if base is None:
                 base = cKDTree(surface_samples(scene.target_pos, scene.tris))
             st = Step(scene, target=make_target(scene))
-            fl = FitLoop(st)
+            fl = FitLoop(st, lap_gamma=lap_gamma)
             g = _capture(fl.silhouette_iteration)
             done, dists = 1, []
             for cp in checkpoints:
