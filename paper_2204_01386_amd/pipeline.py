@@ -51,14 +51,19 @@ def pack_textures(albedo: np.ndarray, nmap: np.ndarray | None) -> np.ndarray:
 class _TwoStreams:
     """With `concurrent` set, independent branches of a step run on a second
     stream (default priority) with a second library context, so that their
-    scratch never meets the main stream's.  Every fork makes the second stream
-    wait for the main one and every join the reverse, so a step stays one
-    ordered unit on the caller's stream, also when it is captured into a
-    graph.  Without it every call goes to the caller's stream.  Which is
-    faster depends on the workload (cross-stream dependencies cost more than
-    they save on small steps): autotune_streams() times both."""
+    scratch never meets the main stream's: the vertex attributes beside the
+    rasterization ("attrs"), the fragment index beside the rest of the
+    forward ("index") and the texel gradients beside the coordinate
+    gradients ("texel").  `concurrent` is False (every call on the caller's
+    stream), True (every branch) or the name of one branch.  Every fork makes
+    the second stream wait for the main one and every join the reverse, so a
+    step stays one ordered unit on the caller's stream, also when it is
+    captured into a graph.  Which is faster depends on the workload
+    (cross-stream dependencies cost more than they save on small steps):
+    autotune_streams() times the schedules."""
 
     concurrent = False
+    _forked = False
 
     def _init_streams(self, dev):
         self._aux = None
@@ -71,35 +76,41 @@ class _TwoStreams:
             self._aux = torch.cuda.Stream(device=self.dev)
         return self._aux
 
-    def _fork(self):
-        if self.concurrent:
+    def _on(self, branch):
+        c = self.concurrent
+        return c is True or (isinstance(c, str) and c == branch)
+
+    def _fork(self, branch):
+        if self._on(branch):
             self.aux.wait_stream(torch.cuda.current_stream())
+            self._forked = True
 
     def _join(self):
-        if self.concurrent:
+        if self._forked:
             torch.cuda.current_stream().wait_stream(self.aux)
+            self._forked = False
 
-    def _h2(self):
-        return (self.ctx2 if self.concurrent else self.ctx).handle
+    def _h2(self, branch):
+        return (self.ctx2 if self._on(branch) else self.ctx).handle
 
-    def _sa(self):
-        return C.c_void_p((self.aux if self.concurrent else torch.cuda.current_stream()).cuda_stream)
+    def _sa(self, branch):
+        return C.c_void_p((self.aux if self._on(branch) else torch.cuda.current_stream()).cuda_stream)
 
-    def _chk2(self, rc, what):
+    def _chk2(self, rc, what, branch):
         if rc != 0:
-            (self.ctx2 if self.concurrent else self.ctx).check(rc, what)
+            (self.ctx2 if self._on(branch) else self.ctx).check(rc, what)
 
     def _texture_bwd(self, tex, desc, coord, S, grad_out, grad_tex, grad_coord, what):
         """Texel gradient (inverse-UV gather) on the second stream and the
         coordinate gradient on the main one, or both in one call."""
         H, W = self.H, self.W
-        if not self.concurrent:
+        if not self._on("texel"):
             self._chk(_lib.dressi_texture_bwd(self.ctx.handle, _p(tex), C.byref(desc), _p(coord), _p(self.tri_id),
                                               S, H, W, _p(grad_out), _p(grad_tex), _p(grad_coord), self._s()), what)
             return
-        self._fork()
-        self._chk2(_lib.dressi_texture_bwd(self._h2(), _p(tex), C.byref(desc), _p(coord), _p(self.tri_id), S, H, W,
-                                           _p(grad_out), _p(grad_tex), None, self._sa()), what)
+        self._fork("texel")
+        self._chk2(_lib.dressi_texture_bwd(self._h2("texel"), _p(tex), C.byref(desc), _p(coord), _p(self.tri_id), S,
+                                           H, W, _p(grad_out), _p(grad_tex), None, self._sa("texel")), what, "texel")
         self._chk(_lib.dressi_texture_bwd(self.ctx.handle, _p(tex), C.byref(desc), _p(coord), _p(self.tri_id), S,
                                           H, W, _p(grad_out), None, _p(grad_coord), self._s()), what + " coord")
 
@@ -275,17 +286,16 @@ class Step(_TwoStreams):
         h, s = self.ctx.handle, self._s()
         B, V, T, H, W, K = self.B, self.V, self.T, self.H, self.W, self.K
         ck = self._chk
-        h2, sa = self._h2(), self._sa()
         # vertex attributes beside transform + rasterization
-        self._fork()
-        self._chk2(_lib.dressi_vertex_attrs(h2, _p(self.pos), _p(self.tris), V, T, _p(self.extra), _p(self.adj),
-                                            _p(self.vattr), sa), "vertex_attrs")
+        self._fork("attrs")
+        self._chk2(_lib.dressi_vertex_attrs(self._h2("attrs"), _p(self.pos), _p(self.tris), V, T, _p(self.extra),
+                                            _p(self.adj), _p(self.vattr), self._sa("attrs")), "vertex_attrs", "attrs")
         self._raster()
         self._join()
         # the backward's fragment index beside the rest of the forward
-        self._fork()
-        self._chk2(_lib.dressi_fragment_index(h2, _p(self.tri_id), B, K, H, W, T, _p(self.frag_index), sa),
-                   "fragment_index")
+        self._fork("index")
+        self._chk2(_lib.dressi_fragment_index(self._h2("index"), _p(self.tri_id), B, K, H, W, T, _p(self.frag_index),
+                                              self._sa("index")), "fragment_index", "index")
         ck(_lib.dressi_interpolate(h, _p(self.vattr), 1, V, self.Cv, _p(self.tris), T, _p(self.tri_id),
                                    _p(self.bary), B, K, H, W, _p(self.gbuf), s), "interpolate")
         if self.uv is not None:
@@ -661,15 +671,14 @@ class BatchStep(_TwoStreams):
     def forward(self):
         h, st = self.ctx.handle, self._s()
         H, W, V, T, ck = self.H, self.W, self.V, self.T, self._chk
-        h2, sa = self._h2(), self._sa()
-        self._fork()
-        self._chk2(_lib.dressi_vertex_attrs(h2, _p(self.pos), _p(self.tris), V, T, None, _p(self.adj),
-                                            _p(self.vattr), sa), "vertex_attrs")
+        self._fork("attrs")
+        self._chk2(_lib.dressi_vertex_attrs(self._h2("attrs"), _p(self.pos), _p(self.tris), V, T, None, _p(self.adj),
+                                            _p(self.vattr), self._sa("attrs")), "vertex_attrs", "attrs")
         self._raster()
         self._join()
-        self._fork()
-        self._chk2(_lib.dressi_fragment_index(h2, _p(self.tri_id), 1, 1, H, W, T, _p(self.frag_index), sa),
-                   "fragment_index")
+        self._fork("index")
+        self._chk2(_lib.dressi_fragment_index(self._h2("index"), _p(self.tri_id), 1, 1, H, W, T, _p(self.frag_index),
+                                              self._sa("index")), "fragment_index", "index")
         ck(_lib.dressi_interpolate(h, _p(self.vattr), 1, V, 6, _p(self.tris), T, _p(self.tri_id), _p(self.bary),
                                    1, 1, H, W, _p(self.gbuf), st), "interpolate")
         ck(_lib.dressi_interpolate(h, _p(self.uv), 1, self.uv.shape[0], 2, _p(self.uv_tris), T, _p(self.tri_id),
@@ -804,11 +813,12 @@ def autotune(step, reps: int = 5) -> dict:
 
 
 def autotune_streams(step, reps: int = 20) -> dict:
-    """Chooses between issuing the whole step on the caller's stream and
-    running its independent branches on a second stream, by timing graph
-    replays of the captured step in each mode (the results are the same)."""
+    """Chooses between issuing the whole step on the caller's stream, running
+    only the fragment index on a second stream, and running every independent
+    branch there, by timing graph replays of the captured step in each mode
+    (the results are the same)."""
     results = {}
-    for mode in (False, True):
+    for mode in (False, "index", True):
         step.concurrent = mode
         side = torch.cuda.Stream()
         side.wait_stream(torch.cuda.current_stream())

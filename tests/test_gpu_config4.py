@@ -89,7 +89,7 @@ def test_batch_config4_full_matches_standalone():
     assert_grad_close(host(bs.view_grads(i)["pos"]), o_g["pos"], what="grad pos")
 
 
-@pytest.mark.parametrize("concurrent", [False, True])
+@pytest.mark.parametrize("concurrent", [False, "index", True])
 def test_batch_deterministic_and_graph_replay(small_batch, concurrent):
     """Replays of the captured step (on one stream, or with its independent
     branches on a second stream) give bitwise the eager single-stream step."""

@@ -194,7 +194,7 @@ def test_step_blend_settings(B, blend, K, r):
     _compare_step(scenes.fit_scene(subdiv=3, H=128, K=K, r=r, blend=blend))
 
 
-@pytest.mark.parametrize("concurrent", [False, True])
+@pytest.mark.parametrize("concurrent", [False, "index", True])
 def test_step_deterministic_and_graph_replay(B, concurrent):
     """The step is bitwise reproducible, also with its independent branches
     (vertex attributes, fragment index, texel gradients of the texture and

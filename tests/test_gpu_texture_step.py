@@ -129,7 +129,7 @@ def test_texture_step_config2_oracle(B):
     assert abs(L - o_g["loss"]) <= 1e-5 * o_g["loss"], (L, o_g["loss"])
 
 
-@pytest.mark.parametrize("concurrent", [False, True])
+@pytest.mark.parametrize("concurrent", [False, "index", True])
 def test_texture_step_graph_replay(B, concurrent):
     from paper_2204_01386_amd.pipeline import Step, TextureStep, make_target
     s = _scene("config3_small")
