@@ -334,6 +334,55 @@ __global__ void k_interp_bwd_vertex(int B, int Ba, int Va, int T, int K, int C, 
     if (live && slot == 0) grad_attr[oi] = s;
 }
 
+// The same sums for a vertex's CC channels at once: one group of IBV_LANES
+// lanes per (view, vertex) walks its corners and their tile lists once and
+// loads each record's CC channels together, instead of one walk per channel.
+// Every channel is summed over the same terms in the same order as above, so
+// the results are bitwise those of k_interp_bwd_vertex.
+template <int CC>
+__global__ void k_interp_bwd_vertex_c(int B, int Ba, int Va, int T, int K, TriTiles tt,
+                                      const float *__restrict__ partial, Adjacency adj,
+                                      float *__restrict__ grad_attr) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t bv = gid / IBV_LANES;   // (ba, v)
+    const int slot = (int)(gid - bv * IBV_LANES);
+    const bool live = bv < (int64_t)Ba * Va;
+    float s[CC];
+#pragma unroll
+    for (int c = 0; c < CC; c++) s[c] = 0.0f;
+    if (live) {
+        const int ba = (int)(bv / Va), v = (int)(bv - (int64_t)ba * Va);
+        const int b0 = (Ba == 1) ? 0 : ba, b1 = (Ba == 1) ? B : ba + 1;
+        for (int j = adj.offsets[v] + slot; j < adj.offsets[v + 1]; j += IBV_LANES) {
+            const int cr = adj.corners[j];
+            const int t = cr / 3, i = cr - 3 * t;
+            float a[CC];
+#pragma unroll
+            for (int c = 0; c < CC; c++) a[c] = 0.0f;
+            for (int b = b0; b < b1; b++) {
+                const int64_t key = (int64_t)b * T + t;
+                for (int e = tt.offsets[key]; e < tt.offsets[key + 1]; e++) {
+                    const int2 ent = tt.entries[e];
+                    const float *pp = partial + ((int64_t)ent.x * DRESSI_TILE_PIX * K + ent.y) * 3 * CC + i * CC;
+#pragma unroll
+                    for (int c = 0; c < CC; c++) a[c] += pp[c];
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < CC; c++) s[c] += a[c];
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < CC; c++) {
+#pragma unroll
+        for (int m = 1; m < IBV_LANES; m <<= 1) s[c] += __shfl_xor(s[c], m, 64);
+    }
+    if (live && slot == 0) {
+#pragma unroll
+        for (int c = 0; c < CC; c++) grad_attr[bv * CC + c] = s[c];
+    }
+}
+
 extern "C" int dressi_interpolate_bwd(dressi_ctx *ctx, const float *attr, int Ba, int Va, int C,
                                       const int32_t *attr_tris, int T, const int32_t *tri_id,
                                       const float *bary, int B, int K, int H, int W,
@@ -397,9 +446,21 @@ extern "C" int dressi_interpolate_bwd(dressi_ctx *ctx, const float *attr, int Ba
                 DR_LAUNCH("k_interp_bwd_tile", (k_interp_bwd_tile<0>), B * nt, DRESSI_TILE_PIX, lds, st, attr, Ba,
                           Va, C, attr_tris, T, tri_id, b2, K, H, W, ntx, nt, fl, grad_out, gbi, gbo, part);
         }
-        int64_t ng = (int64_t)Ba * Va * C;
-        DR_LAUNCH("k_interp_bwd_vertex", (k_interp_bwd_vertex), (int)((ng * IBV_LANES + 255) / 256), 256, 0, st,
-                  B, Ba, Va, T, K, C, tt, part, A, grad_attr);
+        const int64_t nv = (int64_t)Ba * Va, gv = (nv * IBV_LANES + 255) / 256;
+        if (C == 6)
+            DR_LAUNCH("k_interp_bwd_vertex", (k_interp_bwd_vertex_c<6>), (int)gv, 256, 0, st, B, Ba, Va, T, K, tt,
+                      part, A, grad_attr);
+        else if (C == 9)
+            DR_LAUNCH("k_interp_bwd_vertex", (k_interp_bwd_vertex_c<9>), (int)gv, 256, 0, st, B, Ba, Va, T, K, tt,
+                      part, A, grad_attr);
+        else if (C == 3)
+            DR_LAUNCH("k_interp_bwd_vertex", (k_interp_bwd_vertex_c<3>), (int)gv, 256, 0, st, B, Ba, Va, T, K, tt,
+                      part, A, grad_attr);
+        else {
+            int64_t ng = (int64_t)Ba * Va * C;
+            DR_LAUNCH("k_interp_bwd_vertex", (k_interp_bwd_vertex), (int)((ng * IBV_LANES + 255) / 256), 256, 0,
+                      st, B, Ba, Va, T, K, C, tt, part, A, grad_attr);
+        }
     } else if (grad_bary && n > 0) {
         DR_LAUNCH("k_interp_bwd_bary", (k_interp_bwd_bary), (int)((n + 255) / 256), 256, 0, st,
                   attr, Ba, Va, C, attr_tris, T, tri_id, (int64_t)K * H * W, n, grad_out,
