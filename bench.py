@@ -524,6 +524,28 @@ def _tuned_json(t):
             "step_ms": {name[k]: round(v, 4) for k, v in t["streams"]["ms"].items()}}
 
 
+def copy_bandwidth(mib: int = 1024, reps: int = 20) -> dict:
+    """Achieved HBM bandwidth of a plain device-to-device copy of `mib` MiB
+    (read once, written once), the practical ceiling the step's algorithmic
+    bytes are also compared with."""
+    src = torch.ones(mib * (1 << 18), dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"gbs": round(2 * mib * (1 << 20) / (ms * 1e-3) / 1e9, 1), "bytes_per_copy": 2 * mib * (1 << 20),
+            "ms_per_copy": round(ms, 4), "kind": "torch copy_ (device to device), read + write"}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -652,6 +674,15 @@ def main():
                          f"single thread), {tc * 1e3:.1f} ms/step"}
 
     pix = B * scene.H * scene.W
+    cbw = copy_bandwidth()
+
+    def copy_frac(nbytes, ms):
+        return round(nbytes / (ms * 1e-3) / 1e9 / cbw["gbs"], 4)
+
+    if multi:
+        multi["step_copy_frac"] = copy_frac(multi["step_alg_bytes"], multi["ms_per_step"])
+    if uneven and uneven.get("step_alg_bytes"):
+        uneven["step_copy_frac"] = copy_frac(uneven["step_alg_bytes"], uneven["ms_per_step"])
     res = {
         "metric": "fwd+bwd Mpix/s & tris/s at 512^2 80k tris; batched vs plain speedup, %HBM roofline",
         "value": round(pix / (ms_batched * 1e-3) / 1e6, 3),
@@ -678,6 +709,8 @@ def main():
             "note": "textures optimised on fixed geometry: rasterization and inverse-UV map cached"},
         "step_alg_bytes": step_bytes,
         "step_hbm_frac": round(step_bytes / (ms_batched * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "step_copy_frac": copy_frac(step_bytes, ms_batched),
+        "hbm_copy": cbw,
         "roofline": {"bound": "hbm", "kernel": dom[0],
                      "achieved": round(achieved, 2) if achieved else None,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
