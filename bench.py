@@ -528,6 +528,7 @@ def copy_bandwidth(mib: int = 1024, reps: int = 20) -> dict:
     """Achieved HBM bandwidth of a plain device-to-device copy of `mib` MiB
     (read once, written once), the practical ceiling the step's algorithmic
     bytes are also compared with."""
+    import torch
     src = torch.ones(mib * (1 << 18), dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
     for _ in range(3):
