@@ -1,4 +1,4 @@
-// Small device primitives of libdressi: fills, a three-phase exclusive scan,
+// Small device primitives of libdressi: fills, a multi-block exclusive scan,
 // and the vertex -> corner adjacency used by the deterministic gathers.
 #include "dressi_internal.h"
 
@@ -119,6 +119,35 @@ __global__ void __launch_bounds__(SCAN_BS) k_scan_apply(const int32_t *in, int32
     if (blockIdx.x == gridDim.x - 1 && threadIdx.x == SCAN_BS - 1) out[n] = ex;
 }
 
+// The same, where each block first adds up the totals of the blocks before
+// it (at most SCAN_DIRECT_MAX of them, from L2) instead of reading a scanned
+// copy: one launch fewer than reduce, scan of the totals, apply.
+#define SCAN_DIRECT_MAX 2048
+__global__ void __launch_bounds__(SCAN_BS) k_scan_apply_direct(const int32_t *in, int32_t *out, int64_t n,
+                                                               const int32_t *block_sums) {
+    __shared__ int wsum[SCAN_BS / 64];
+    int pre = 0;
+    for (int j = threadIdx.x; j < (int)blockIdx.x; j += SCAN_BS) pre += block_sums[j];
+    int offset;
+    block_exclusive_scan<SCAN_BS>(pre, offset, wsum);
+    int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK + (int64_t)threadIdx.x * SCAN_PER;
+    int v[SCAN_PER];
+    int s = 0;
+#pragma unroll
+    for (int j = 0; j < SCAN_PER; j++) {
+        v[j] = (base + j < n) ? in[base + j] : 0;
+        s += v[j];
+    }
+    int total;
+    int ex = block_exclusive_scan<SCAN_BS>(s, total, wsum) + offset;
+#pragma unroll
+    for (int j = 0; j < SCAN_PER; j++) {
+        if (base + j < n) out[base + j] = ex;
+        ex += v[j];
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == SCAN_BS - 1) out[n] = ex;
+}
+
 // whole scan in one workgroup (small n): chunks of 4096 with a running carry
 __global__ void __launch_bounds__(1024) k_scan_single(const int32_t *in, int32_t *out, int64_t n) {
     __shared__ int wsum[16];
@@ -165,6 +194,10 @@ void dressi_exclusive_scan(const int32_t *in, int32_t *out, int64_t n, void *tmp
     int nb = (int)((n + SCAN_CHUNK - 1) / SCAN_CHUNK);
     int32_t *sums = static_cast<int32_t *>(tmp);
     DR_LAUNCH("k_scan_reduce", (k_scan_reduce), nb, SCAN_BS, 0, s, in, n, sums);
+    if (nb <= SCAN_DIRECT_MAX) {
+        DR_LAUNCH("k_scan_apply", (k_scan_apply_direct), nb, SCAN_BS, 0, s, in, out, n, sums);
+        return;
+    }
     DR_LAUNCH("k_scan_blocks", (k_scan_blocks), 1, 1024, 0, s, sums, nb);
     DR_LAUNCH("k_scan_apply", (k_scan_apply), nb, SCAN_BS, 0, s, in, out, n, sums);
 }
