@@ -524,6 +524,21 @@ def _tuned_json(t):
             "step_ms": {name[k]: round(v, 4) for k, v in t["streams"]["ms"].items()}}
 
 
+def _host_cpu() -> str:
+    """The host CPU's model name and the number of logical CPUs this process may use."""
+    model = "unknown CPU"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return f"{model} ({n} logical CPUs available)"
+
+
 def copy_bandwidth(mib: int = 1024, reps: int = 20) -> dict:
     """Achieved HBM bandwidth of a plain device-to-device copy of `mib` MiB
     (read once, written once), the practical ceiling the step's algorithmic
@@ -672,7 +687,7 @@ def main():
         cpu = {"value": round(B * scene.H * scene.W / tc / 1e6, 4), "unit": "Mpix/s", "cores": 1,
                "kind": "oracle",
                "sample": f"{nrun} full fwd+bwd steps of the same workload (C oracle, fp64, "
-                         f"single thread), {tc * 1e3:.1f} ms/step"}
+                         f"single thread), {tc * 1e3:.1f} ms/step, on {_host_cpu()}"}
 
     pix = B * scene.H * scene.W
     cbw = copy_bandwidth()
