@@ -108,7 +108,7 @@ static inline Adjacency adjacency_view(const int32_t *buf, int V) {
     return a;
 }
 static inline size_t adjacency_buf_bytes(int V, int T) { return sizeof(int32_t) * ((size_t)V + 1 + 3 * (size_t)T); }
-size_t dressi_adjacency_tmp_bytes(int V);
+size_t dressi_adjacency_tmp_bytes(int V, int T);
 void dressi_build_adjacency_into(const int32_t *tris, int T, int V, int32_t *buf, void *tmp,
                                  hipStream_t s);
 

@@ -402,7 +402,7 @@ extern "C" int dressi_interpolate_bwd(dressi_ctx *ctx, const float *attr, int Ba
         size_t o_fi = frag_index ? 0 : c.take(dressi_fragindex_bytes(B, K, H, W, T));
         size_t o_adj = adj ? 0 : c.take(adjacency_buf_bytes(Va, T));
         size_t o_tmp = c.take(std::max(frag_index ? (size_t)0 : dressi_fragindex_tmp_bytes(B, K, H, W, T),
-                                       adj ? (size_t)0 : dressi_adjacency_tmp_bytes(Va)));
+                                       adj ? (size_t)0 : dressi_adjacency_tmp_bytes(Va, T)));
         size_t o_part = c.take(sizeof(float) * (size_t)B * nt * DRESSI_TILE_PIX * K * 3 * C);
         rc = dressi_scratch(ctx, c.off, st);
         if (rc) return rc;

@@ -213,7 +213,7 @@ extern "C" int dressi_laplacian_reg(dressi_ctx *ctx, const float *pos, const int
     const int nb = (V + LAP_BS - 1) / LAP_BS;
     Carver c;
     size_t o_adj = adj ? 0 : c.take(adjacency_buf_bytes(V, T));
-    size_t o_tmp = adj ? 0 : c.take(dressi_adjacency_tmp_bytes(V));
+    size_t o_tmp = adj ? 0 : c.take(dressi_adjacency_tmp_bytes(V, T));
     size_t o_dw = c.take(sizeof(float4) * (size_t)V);
     size_t o_part = c.take(sizeof(double) * (size_t)nb);
     int rc = dressi_scratch(ctx, c.off, st);

@@ -205,8 +205,9 @@ void dressi_exclusive_scan(const int32_t *in, int32_t *out, int64_t n, void *tmp
 // ---------------------------------------------------------------------------
 // vertex -> corner adjacency (CSR), each vertex's corners in ascending order
 // ---------------------------------------------------------------------------
-__global__ void k_count_corners(const int32_t *tris, int64_t n3, int V, int32_t *counts) {
+__global__ void k_count_corners(const int32_t *tris, int64_t n3, int V, int32_t *counts, int32_t *nlong) {
     int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c == 0) *nlong = 0;   // the long-list queue of k_sort_corners, read after this launch
     if (c >= n3) return;
     int v = tris[c];
     if (v >= 0 && v < V) atomicAdd(&counts[v], 1);
@@ -222,12 +223,21 @@ __global__ void k_place_corners(const int32_t *tris, int64_t n3, int V, const in
     corners[slot] = (int32_t)c;
 }
 
-// the atomics above place corners in arbitrary order: sort every list so that
-// gathers sum in a fixed order
-__global__ void k_sort_corners(const int32_t *offsets, int32_t *corners, int V) {
+// The atomics above place corners in arbitrary order: every list is sorted so
+// that gathers sum in a fixed order.  Lists of up to ADJ_SHORT corners are
+// insertion-sorted by one thread; longer ones (a vertex of high valence) are
+// queued for k_sort_corners_long, at most n3 / (ADJ_SHORT + 1) of them.
+#define ADJ_SHORT 64
+__global__ void k_sort_corners(const int32_t *offsets, int32_t *corners, int V, int32_t *nlong,
+                               int32_t *longv, int cap) {
     int v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= V) return;
     int a = offsets[v], b = offsets[v + 1];
+    if (b - a > ADJ_SHORT) {
+        const int q = atomicAdd(nlong, 1);
+        if (q < cap) longv[q] = v;
+        return;
+    }
     for (int i = a + 1; i < b; i++) {
         int x = corners[i];
         int j = i - 1;
@@ -239,11 +249,52 @@ __global__ void k_sort_corners(const int32_t *offsets, int32_t *corners, int V) 
     }
 }
 
-size_t dressi_adjacency_tmp_bytes(int V) {
+// One workgroup per queued list: a bottom-up merge sort between the list and
+// its stretch of `tmp`, runs of width 1, 2, 4, ...  The corner indices of a
+// list are distinct, so each corner's place in its merged pair of runs is its
+// rank in its own run plus the number of smaller corners in the other run,
+// found by binary search.
+__global__ void __launch_bounds__(1024) k_sort_corners_long(const int32_t *offsets, int32_t *corners, int32_t *tmp,
+                                                           const int32_t *nlong, const int32_t *longv, int cap) {
+    const int nq = min(*nlong, cap);
+    for (int q = blockIdx.x; q < nq; q += gridDim.x) {
+        const int v = longv[q];
+        const int a = offsets[v], n = offsets[v + 1] - a;
+        int32_t *src = corners + a, *dst = tmp + a;
+        for (int w = 1; w < n; w <<= 1) {
+            for (int i = threadIdx.x; i < n; i += blockDim.x) {
+                const int x = src[i];
+                const int r = i / w;
+                const int own = r * w, base = (r & ~1) * w;
+                const int ps = (r ^ 1) * w, pe = min(ps + w, n);
+                int lo = ps, hi = max(ps, pe);
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if (src[mid] < x) lo = mid + 1;
+                    else hi = mid;
+                }
+                dst[base + (i - own) + (lo - ps)] = x;
+            }
+            __syncthreads();
+            int32_t *t = src;
+            src = dst;
+            dst = t;
+        }
+        if (src != corners + a)
+            for (int i = threadIdx.x; i < n; i += blockDim.x) corners[a + i] = src[i];
+        __syncthreads();
+    }
+}
+
+static size_t adj_long_cap(int T) { return 3 * (size_t)T / (ADJ_SHORT + 1) + 1; }
+
+size_t dressi_adjacency_tmp_bytes(int V, int T) {
     Carver c;
-    c.take(sizeof(int32_t) * (size_t)V);   // counts
-    c.take(sizeof(int32_t) * (size_t)V);   // cursor
+    c.take(sizeof(int32_t) * (size_t)V);                     // counts
+    c.take(sizeof(int32_t) * (size_t)V);                     // cursor
     c.take(dressi_scan_tmp_bytes(V));
+    c.take(sizeof(int32_t) * (1 + adj_long_cap(T)));         // long-list queue: count, vertices
+    c.take(sizeof(int32_t) * 3 * (size_t)T);                 // merge-sort buffer
     return c.off;
 }
 
@@ -254,14 +305,25 @@ void dressi_build_adjacency_into(const int32_t *tris, int T, int V, int32_t *buf
     int32_t *counts = at<int32_t>(tmp, c.take(sizeof(int32_t) * (size_t)V));
     int32_t *cursor = at<int32_t>(tmp, c.take(sizeof(int32_t) * (size_t)V));
     void *stmp = at<void>(tmp, c.take(dressi_scan_tmp_bytes(V)));
+    const int cap = (int)adj_long_cap(T);
+    int32_t *nlong = at<int32_t>(tmp, c.take(sizeof(int32_t) * (1 + (size_t)cap)));
+    int32_t *longv = nlong + 1;
+    int32_t *sbuf = at<int32_t>(tmp, c.take(sizeof(int32_t) * 3 * (size_t)T));
     int64_t n3 = 3 * (int64_t)T;
     dressi_fill_i32(counts, 0, 2 * (int64_t)((sizeof(int32_t) * (size_t)V + 255) / 256 * 64), s);
-    if (n3 > 0) DR_LAUNCH("k_count_corners", (k_count_corners), (int)((n3 + 255) / 256), 256, 0, s, tris, n3, V, counts);
+    if (n3 > 0)
+        DR_LAUNCH("k_count_corners", (k_count_corners), (int)((n3 + 255) / 256), 256, 0, s, tris, n3, V, counts,
+                  nlong);
     dressi_exclusive_scan(counts, adj.offsets, V, stmp, s);
     if (n3 > 0)
         DR_LAUNCH("k_place_corners", (k_place_corners), (int)((n3 + 255) / 256), 256, 0, s, tris, n3, V, adj.offsets, cursor,
                                                                adj.corners);
-    if (V > 0) DR_LAUNCH("k_sort_corners", (k_sort_corners), (V + 255) / 256, 256, 0, s, adj.offsets, adj.corners, V);
+    if (V > 0 && n3 > 0) {
+        DR_LAUNCH("k_sort_corners", (k_sort_corners), (V + 255) / 256, 256, 0, s, adj.offsets, adj.corners, V, nlong,
+                  longv, cap);
+        DR_LAUNCH("k_sort_corners", (k_sort_corners_long), 64, 1024, 0, s, adj.offsets, adj.corners, sbuf, nlong,
+                  longv, cap);
+    }
 }
 
 extern "C" int dressi_adjacency(dressi_ctx *ctx, const int32_t *tris, int T, int V, int32_t *adj,
@@ -270,7 +332,7 @@ extern "C" int dressi_adjacency(dressi_ctx *ctx, const int32_t *tris, int T, int
     if (T < 0 || V < 0) return dressi_fail(ctx, DRESSI_EINVAL, "adjacency: bad dimensions");
     if (!adj || (T > 0 && !tris)) return dressi_fail(ctx, DRESSI_EINVAL, "adjacency: null pointer");
     hipStream_t st = (hipStream_t)stream;
-    int rc = dressi_scratch(ctx, dressi_adjacency_tmp_bytes(V), st);
+    int rc = dressi_scratch(ctx, dressi_adjacency_tmp_bytes(V, T), st);
     if (rc) return rc;
     dressi_build_adjacency_into(tris, T, V, adj, ctx->scratch, st);
     return dressi_launch_check(ctx, "adjacency");

@@ -1387,7 +1387,7 @@ static int rasterize_bwd_impl(dressi_ctx *ctx, const float *pos_clip, const int3
     size_t o_fi = frag_index ? 0 : c.take(dressi_fragindex_bytes(B, K, H, W, T));
     size_t o_adj = adj ? 0 : c.take(adjacency_buf_bytes(V, T));
     size_t o_tmp = c.take(std::max(frag_index ? (size_t)0 : dressi_fragindex_tmp_bytes(B, K, H, W, T),
-                                   adj ? (size_t)0 : dressi_adjacency_tmp_bytes(V)));
+                                   adj ? (size_t)0 : dressi_adjacency_tmp_bytes(V, T)));
     size_t o_part = c.take(sizeof(float) * partial_floats(B, K, H, W, 9));
     rc = dressi_scratch(ctx, c.off, st);
     if (rc) return rc;
@@ -1467,7 +1467,7 @@ extern "C" size_t dressi_scratch_bytes(int B, int V, int T, int H, int W, int K,
         Carver c;
         c.take(dressi_fragindex_bytes(B, K, H, W, T));
         c.take(adjacency_buf_bytes(Vm, T));
-        c.take(std::max(dressi_fragindex_tmp_bytes(B, K, H, W, T), dressi_adjacency_tmp_bytes(Vm)));
+        c.take(std::max(dressi_fragindex_tmp_bytes(B, K, H, W, T), dressi_adjacency_tmp_bytes(Vm, T)));
         c.take(sizeof(float) * 3 * (size_t)(C > 9 ? C : 9) * B * T);
         c.take(sizeof(float) * partial_floats(B, K, H, W, 3 * (C > 3 ? C : 3)));
         upd(c.off);

@@ -258,7 +258,7 @@ extern "C" int dressi_vertex_attrs(dressi_ctx *ctx, const float *pos, const int3
     if (!ab) {
         Carver c;
         size_t o_adj = c.take(adjacency_buf_bytes(V, T));
-        size_t o_tmp = c.take(dressi_adjacency_tmp_bytes(V));
+        size_t o_tmp = c.take(dressi_adjacency_tmp_bytes(V, T));
         int rc = dressi_scratch(ctx, c.off, st);
         if (rc) return rc;
         int32_t *buf = at<int32_t>(ctx->scratch, o_adj);
@@ -284,7 +284,7 @@ extern "C" int dressi_vertex_attrs_bwd(dressi_ctx *ctx, const float *pos, const 
     hipStream_t st = (hipStream_t)stream;
     Carver c;
     size_t o_adj = adj ? 0 : c.take(adjacency_buf_bytes(V, T));
-    size_t o_tmp = adj ? 0 : c.take(dressi_adjacency_tmp_bytes(V));
+    size_t o_tmp = adj ? 0 : c.take(dressi_adjacency_tmp_bytes(V, T));
     size_t o_ga = c.take(sizeof(float) * 3 * (size_t)V);
     int rc = dressi_scratch(ctx, c.off, st);
     if (rc) return rc;

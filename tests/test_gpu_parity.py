@@ -443,3 +443,51 @@ def test_shared_index_and_adjacency_match_internal_builds(B):
     a1, b1 = B.dressi_interpolate_bwd(attr, dev(tris), tid, bary, go)
     a2, b2 = B.dressi_interpolate_bwd(attr, dev(tris), tid, bary, go, frag_index=fi, adj=adj)
     assert np.array_equal(host(a1), host(a2)) and np.array_equal(host(b1), host(b2))
+
+
+@pytest.mark.parametrize("n_keys", [2048 * 1024, 2048 * 1024 + 1])
+def test_fragment_index_scan_across_many_blocks(B, n_keys):
+    """The triangle -> tiles offsets are an exclusive scan over every (view,
+    triangle) count.  A small scene rendered after n_keys - T0 off-screen
+    triangles (ids shifted by the padding, counts all zero before them) gives
+    the same fragments, bitwise the same position and attribute gradients on
+    its own vertices and zero on the padding's: the scan carries the zero
+    prefix across 2,048 blocks of 1,024 counts (the largest single-pass form)
+    and across 2,049 (the form that scans the block totals separately).  The
+    padding shares three vertices, each of valence n_pad: their corner lists
+    take the adjacency's long-list sort, checked against numpy."""
+    pc, tris = sphere_scene(subdiv=3, seed=3)
+    V, T0 = pc.shape[1], len(tris)
+    n_pad = n_keys - T0
+    off = np.array([[5.0, 5.0, 0.5, 1.0], [6.0, 5.0, 0.5, 1.0], [5.0, 6.0, 0.5, 1.0]], np.float32)
+    pc_p = np.concatenate([pc, off[None]], 1)
+    pad = np.broadcast_to(np.array([V, V + 1, V + 2], np.int32), (n_pad, 3))
+    tris_p = np.concatenate([pad, tris]).astype(np.int32)
+    H, W, K, r = 64, 64, 2, 0.03
+    tid, bary, dist = B.dressi_rasterize(dev(pc), dev(tris), H, W, K, r, 0)
+    tid_p, bary_p, dist_p = B.dressi_rasterize(dev(pc_p), dev(tris_p), H, W, K, r, 0)
+    t, tp = host(tid), host(tid_p)
+    assert (t >= 0).sum() > 1000
+    assert np.array_equal(np.where(tp >= 0, tp - n_pad, -1), t)
+    assert np.array_equal(host(bary_p), host(bary)) and np.array_equal(host(dist_p), host(dist))
+    gen = torch.Generator(device="cuda").manual_seed(7)
+    g = torch.randn(bary.shape, device="cuda", generator=gen)
+    gd = torch.randn(dist.shape, device="cuda", generator=gen)
+    gp = host(B.dressi_rasterize_bwd(dev(pc), dev(tris), tid, g, gd, r))
+    adj = B.dressi_adjacency(dev(tris_p), V + 3)
+    a = host(adj)
+    offs, corners = a[:V + 4], a[V + 4:]
+    flat = tris_p.ravel()
+    for v in [0, 17, V - 1, V, V + 1, V + 2]:
+        assert np.array_equal(corners[offs[v]:offs[v + 1]], np.nonzero(flat == v)[0])
+    gp_p = host(B.dressi_rasterize_bwd(dev(pc_p), dev(tris_p), tid_p, g, gd, r, adj=adj))
+    assert np.abs(gp).max() > 0
+    assert np.array_equal(gp_p[:, :V], gp) and not gp_p[:, V:].any()
+    attr = torch.randn((V + 3, 6), device="cuda", generator=gen)
+    go = torch.randn(tid.shape + (6,), device="cuda", generator=gen)
+    ga, gb = B.dressi_interpolate_bwd(attr[:V].contiguous(), dev(tris), tid, bary, go)
+    ga_p, gb_p = B.dressi_interpolate_bwd(attr, dev(tris_p), tid_p, bary_p, go, adj=adj)
+    ga, ga_p = host(ga), host(ga_p)
+    assert np.abs(ga).max() > 0
+    assert np.array_equal(ga_p[:V], ga) and not ga_p[V:].any()
+    assert np.array_equal(host(gb_p), host(gb))
