@@ -295,6 +295,25 @@ int dressi_softras_bwd(dressi_ctx *ctx, const float *color, const float *dist,
                        float *grad_layer_color, float *grad_dist, void *stream);
 
 
+/* Allocation-free variant of dressi_softras, for callers that cannot
+ * allocate device memory at all (code under hipGraph capture that must not
+ * grow the context's arena, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, results and errors as dressi_softras; the two
+ * one-byte-per-pixel edge-mask planes (boundary and row dilation) live in a
+ * fixed device array of the library, 2 * DRESSI_SOFTRAS_NOALLOC_MAX_PIXELS
+ * bytes (32 MiB) per device, held from the first dressi_create on that
+ * device until the process ends.  It calls no allocator.  B*H*W above
+ * DRESSI_SOFTRAS_NOALLOC_MAX_PIXELS returns DRESSI_EINVAL (use
+ * dressi_softras).  Every call on one device shares that device's array and
+ * fully rewrites the part it reads, so calls that overlap in time on one
+ * device (concurrent streams, or several host threads) race and must be
+ * ordered by the caller; calls on one stream are ordered by it. */
+#define DRESSI_SOFTRAS_NOALLOC_MAX_PIXELS (16 * 1024 * 1024)
+int dressi_softras_noalloc(dressi_ctx *ctx, const float *color, const float *dist,
+                           const int32_t *tri_id, int B, int K, int H, int W, int Cc, float sigma,
+                           float delta, int mode, float *out_color, float *out_sil,
+                           uint8_t *edge_mask, void *stream);
+
 /* ----------------------------------------------------------------------------
  * The rest of one rendering step around the four stages above (the paper's
  * decomposition I = f_pp(f_shade(f_rasterize(...))), §3.4.1, and the

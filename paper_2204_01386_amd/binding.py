@@ -100,6 +100,7 @@ _SIG = {
     "dressi_texture_grad_invuv": [_vp, C.POINTER(TexDesc), _vp, _vp, _i, _i, _i, _vp, _vp, _vp, _vp],
     "dressi_softras": [_vp, _vp, _vp, _vp, _i, _i, _i, _i, _i, _f, _f, _i, _vp, _vp, _vp, _vp],
     "dressi_softras_bwd": [_vp, _vp, _vp, _vp, _i, _i, _i, _i, _i, _f, _vp, _vp, _vp, _vp, _vp, _vp],
+    "dressi_softras_noalloc": [_vp, _vp, _vp, _vp, _i, _i, _i, _i, _i, _f, _f, _i, _vp, _vp, _vp, _vp],
     "dressi_transform": [_vp, _vp, _vp, _i, _i, _vp, _vp],
     "dressi_transform_bwd": [_vp, _vp, _i, _i, _vp, _vp, _vp],
     "dressi_vertex_attrs": [_vp, _vp, _vp, _i, _i, _vp, _vp, _vp, _vp],
@@ -479,6 +480,36 @@ def dressi_softras(color, dist, tri_id, sigma, delta, mode=BLEND_HSR):
     ctx.check(_lib.dressi_softras(ctx.handle, _ptr(color), _ptr(dist), _ptr(tri_id), B, K, H, W, Cc,
                                   float(sigma), float(delta), int(mode), _ptr(oc), _ptr(os_), _ptr(E),
                                   _stream()), "dressi_softras")
+    return oc, os_, E
+
+
+SOFTRAS_NOALLOC_MAX_PIXELS = 16 * 1024 * 1024
+
+
+def dressi_softras_noalloc(color, dist, tri_id, sigma, delta, mode=BLEND_HSR, out=None):
+    """dressi_softras through its allocation-free entry point.  `out` =
+    (out_color [B,H,W,Cc], out_sil [B,H,W], edge_mask [B,H,W] uint8) given by
+    the caller, or None to allocate them here (the library call allocates
+    nothing either way)."""
+    _need(color, torch.float32, "color")
+    _need(tri_id, torch.int32, "tri_id")
+    if dist is not None:
+        _need(dist, torch.float32, "dist")
+    B, K, H, W = tri_id.shape
+    Cc = color.shape[-1]
+    dev = color.device
+    if out is None:
+        out = (torch.empty((B, H, W, Cc), dtype=torch.float32, device=dev),
+               torch.empty((B, H, W), dtype=torch.float32, device=dev),
+               torch.empty((B, H, W), dtype=torch.uint8, device=dev))
+    oc, os_, E = out
+    _need(oc, torch.float32, "out_color")
+    _need(os_, torch.float32, "out_sil")
+    _need(E, torch.uint8, "edge_mask")
+    ctx = context(dev.index)
+    ctx.check(_lib.dressi_softras_noalloc(ctx.handle, _ptr(color), _ptr(dist), _ptr(tri_id), B, K, H, W, Cc,
+                                          float(sigma), float(delta), int(mode), _ptr(oc), _ptr(os_),
+                                          _ptr(E), _stream()), "dressi_softras_noalloc")
     return oc, os_, E
 
 

@@ -29,6 +29,12 @@ extern "C" int dressi_create(dressi_ctx **out, int device) {
     if (e == hipSuccess) e = hipMemset(ctx->status, 0, 4 * sizeof(int64_t));
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
+        if (ctx->status) (void)hipFree(ctx->status);
+        delete ctx;
+        return DRESSI_EHIP;
+    }
+    if (dressi_softras_noalloc_setup(device) != DRESSI_OK) {
+        (void)hipFree(ctx->status);
         delete ctx;
         return DRESSI_EHIP;
     }

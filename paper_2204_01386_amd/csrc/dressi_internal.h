@@ -36,6 +36,9 @@ int dressi_hip_check(dressi_ctx *ctx, hipError_t e, const char *what);
 // fails with DRESSI_ENOMEM while `stream` is capturing.
 int dressi_scratch(dressi_ctx *ctx, size_t bytes, hipStream_t stream);
 int dressi_launch_check(dressi_ctx *ctx, const char *what);
+// Looks up, once per device, the device address of the fixed scratch of
+// dressi_softras_noalloc (softras.hip); `device` must be current.
+int dressi_softras_noalloc_setup(int device);
 // Makes sure ctx->counters holds at least n int32 counters, all zero.  The
 // kernels that use them count up and then back down (or reset what they
 // read), so they are zero again when a call ends.  Grows only outside

@@ -6,6 +6,8 @@
 // exact.  The column pass is fused with the per-pixel blend.
 #include "dressi_internal.h"
 
+#include <mutex>
+
 __device__ __forceinline__ bool front_hard(const int32_t *tri_id, const float *dist, int64_t o) {
     if (tri_id[o] < 0) return false;
     if (!dist) return true;
@@ -213,6 +215,29 @@ static int check_softras(dressi_ctx *ctx, const void *color, const void *tid, in
     default: { constexpr int KK = 5; __VA_ARGS__; } break; \
     }
 
+// The edge mask and blend, given the two one-byte-per-pixel planes the edge
+// mask needs (bnd: the boundary, rows: its row-dilated form; unused when the
+// mode needs no dilation).  Shared by dressi_softras and its allocation-free
+// variant.
+static void softras_launch(const float *color, const float *dist, const int32_t *tri_id, int B, int K, int H,
+                           int W, int Cc, float sigma, int rho, int mode, uint8_t *bnd, uint8_t *rows,
+                           float *out_color, float *out_sil, uint8_t *edge_mask, hipStream_t st) {
+    const int64_t n = (int64_t)B * H * W;
+    const int g = (int)((n + 255) / 256);
+    if (rows) {
+        DR_LAUNCH("k_boundary", (k_boundary), g, 256, 0, st, tri_id, dist, B, K, H, W, bnd);
+        DR_LAUNCH("k_dilate_rows", (k_dilate_rows), g, 256, 0, st, bnd, B, H, W, rho, rows);
+    }
+    const float inv_sigma = mode == DRESSI_BLEND_HARD ? 0.0f : 1.0f / sigma;
+    KDISPATCH(K, DR_LAUNCH("k_blend", (k_blend<KK>), g, 256, 0, st, color, dist, tri_id, B, H, W, Cc, inv_sigma, mode,
+                                                 rho, rows, out_color, out_sil, edge_mask));
+}
+
+static bool softras_needs_planes(int mode, float delta, int W, int *rho) {
+    *rho = mode == DRESSI_BLEND_HSR ? (int)ceilf(delta * (float)W) - 1 : 0;
+    return (mode == DRESSI_BLEND_HSR || mode == DRESSI_BLEND_AA) && *rho >= 0;
+}
+
 extern "C" int dressi_softras(dressi_ctx *ctx, const float *color, const float *dist,
                               const int32_t *tri_id, int B, int K, int H, int W, int Cc,
                               float sigma, float delta, int mode, float *out_color, float *out_sil,
@@ -225,25 +250,77 @@ extern "C" int dressi_softras(dressi_ctx *ctx, const float *color, const float *
         return dressi_fail(ctx, DRESSI_EINVAL, "softras: null output");
     hipStream_t st = (hipStream_t)stream;
     int rho = 0;
-    if (mode == DRESSI_BLEND_HSR) rho = (int)ceilf(delta * (float)W) - 1;
-    uint8_t *rows = nullptr;
-    if ((mode == DRESSI_BLEND_HSR || mode == DRESSI_BLEND_AA) && rho >= 0) {
+    uint8_t *bnd = nullptr, *rows = nullptr;
+    if (softras_needs_planes(mode, delta, W, &rho)) {
         Carver c;
         size_t o_b = c.take((size_t)n);
         size_t o_r = c.take((size_t)n);
         rc = dressi_scratch(ctx, c.off, st);
         if (rc) return rc;
-        uint8_t *bnd = at<uint8_t>(ctx->scratch, o_b);
+        bnd = at<uint8_t>(ctx->scratch, o_b);
         rows = at<uint8_t>(ctx->scratch, o_r);
-        int g = (int)((n + 255) / 256);
-        DR_LAUNCH("k_boundary", (k_boundary), g, 256, 0, st, tri_id, dist, B, K, H, W, bnd);
-        DR_LAUNCH("k_dilate_rows", (k_dilate_rows), g, 256, 0, st, bnd, B, H, W, rho, rows);
     }
-    float inv_sigma = mode == DRESSI_BLEND_HARD ? 0.0f : 1.0f / sigma;
-    int g = (int)((n + 255) / 256);
-    KDISPATCH(K, DR_LAUNCH("k_blend", (k_blend<KK>), g, 256, 0, st, color, dist, tri_id, B, H, W, Cc, inv_sigma, mode,
-                                                 rho, rows, out_color, out_sil, edge_mask));
+    softras_launch(color, dist, tri_id, B, K, H, W, Cc, sigma, rho, mode, bnd, rows, out_color, out_sil,
+                   edge_mask, st);
     return dressi_launch_check(ctx, "softras");
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free variant of dressi_softras: the two edge-mask planes live in
+// a fixed device array of the library instead of the context's arena.  In
+// host code `scratch` names a host-side stand-in, never the device memory:
+// its device address is looked up once per device (with that device current)
+// when the library is set up on it, and only that address is passed on.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) uint8_t scratch[2 * (size_t)DRESSI_SOFTRAS_NOALLOC_MAX_PIXELS];
+
+#define NOALLOC_MAX_DEVICES 64
+static std::mutex g_noalloc_mu;
+static uint8_t *g_noalloc_ptr[NOALLOC_MAX_DEVICES];
+
+// Called by dressi_create with `device` current.
+int dressi_softras_noalloc_setup(int device) {
+    if (device < 0 || device >= NOALLOC_MAX_DEVICES) return DRESSI_EINVAL;
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (g_noalloc_ptr[device]) return DRESSI_OK;
+    void *p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return DRESSI_EHIP;
+    g_noalloc_ptr[device] = static_cast<uint8_t *>(p);
+    return DRESSI_OK;
+}
+
+extern "C" int dressi_softras_noalloc(dressi_ctx *ctx, const float *color, const float *dist,
+                                      const int32_t *tri_id, int B, int K, int H, int W, int Cc,
+                                      float sigma, float delta, int mode, float *out_color, float *out_sil,
+                                      uint8_t *edge_mask, void *stream) {
+    int rc = check_softras(ctx, color, tri_id, B, K, H, W, Cc, sigma, mode);
+    if (rc) return rc;
+    int64_t n = (int64_t)B * H * W;
+    if (n == 0) return DRESSI_OK;
+    if (!out_color || !out_sil || !edge_mask)
+        return dressi_fail(ctx, DRESSI_EINVAL, "softras_noalloc: null output");
+    if (n > DRESSI_SOFTRAS_NOALLOC_MAX_PIXELS)
+        return dressi_fail(ctx, DRESSI_EINVAL,
+                           "softras_noalloc: B*H*W = " + std::to_string(n) + " exceeds the fixed scratch's " +
+                               std::to_string((int64_t)DRESSI_SOFTRAS_NOALLOC_MAX_PIXELS) +
+                               " pixels; use dressi_softras");
+    uint8_t *base = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_noalloc_mu);
+        if (ctx->device >= 0 && ctx->device < NOALLOC_MAX_DEVICES) base = g_noalloc_ptr[ctx->device];
+    }
+    if (!base)
+        return dressi_fail(ctx, DRESSI_EHIP, "softras_noalloc: the fixed scratch of this device was not set up");
+    int rho = 0;
+    uint8_t *bnd = nullptr, *rows = nullptr;
+    if (softras_needs_planes(mode, delta, W, &rho)) {
+        bnd = base;
+        rows = base + DRESSI_SOFTRAS_NOALLOC_MAX_PIXELS;
+    }
+    softras_launch(color, dist, tri_id, B, K, H, W, Cc, sigma, rho, mode, bnd, rows, out_color, out_sil,
+                   edge_mask, (hipStream_t)stream);
+    return dressi_launch_check(ctx, "softras_noalloc");
 }
 
 extern "C" int dressi_softras_bwd(dressi_ctx *ctx, const float *color, const float *dist,
