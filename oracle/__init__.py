@@ -479,3 +479,19 @@ def interpolate_f32(attr, attr_tris, tri_id, bary):
     _check(f(_p(a), Va, Cc, _p(at), at.shape[0], _p(tid), _p(_f32(bary)), tid.size, _p(out)),
            "interpolate_f32")
     return out
+
+
+def texture_f32(tex, coord, tri_id=None, kind=TEX_2D, wrap_u=WRAP_REPEAT, wrap_v=WRAP_CLAMP):
+    """Bilinear sample in float32 with a fixed operation order (for values
+    that feed discrete decisions downstream)."""
+    t = _f32(tex)
+    d = _desc(t, kind, wrap_u, wrap_v)
+    c = _f32(coord)
+    cd = c.shape[-1]
+    N = c.size // cd
+    out = np.empty(c.shape[:-1] + (d.Ct,), np.float32)
+    f = lib().orc_texture_f32
+    f.argtypes = [C.c_void_p, C.POINTER(_TexDesc), C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]
+    tid = _i32(tri_id) if tri_id is not None else None
+    _check(f(_p(t), C.byref(d), _p(c), _p(tid), N, _p(out)), "texture_f32")
+    return out

@@ -1447,3 +1447,38 @@ int orc_interpolate_f32(const float *attr, int Va, int C, const int32_t *attr_tr
     (void)Va;
     return 0;
 }
+
+/* Bilinear sample (2-D or cube) in float: the taps and fractions of
+ * tex_taps, weights w00 = (1-fy)(1-fx), w01 = (1-fy)fx, w10 = fy(1-fx),
+ * w11 = fy fx, and out = ((w00 t00 + w01 t01) + w10 t10) + w11 t11.  A
+ * tangent-space normal-map sample feeds the shading normal, whose direction
+ * selects cube texels and the side of the max(0, .) kinks, so it is taken
+ * in this order on both sides. */
+int orc_texture_f32(const float *tex, const orc_tex_desc *td, const float *coord,
+                    const int32_t *tri_id, int64_t N, float *out)
+{
+    int cd = td->kind == ORC_TEX_CUBE ? 3 : 2;
+    int Ct = td->Ct;
+    for (int64_t i = 0; i < N; i++) {
+        float *y = out + i * Ct;
+        for (int c = 0; c < Ct; c++) y[c] = 0.0f;
+        if (tri_id && tri_id[i] < 0) continue;
+        otap t = tex_taps(td, coord + i * cd);
+        if (!t.ok) continue;
+        const float fx = (float)t.fx, fy = (float)t.fy;
+        const float gx = 1.0f - fx, gy = 1.0f - fy;
+        const float w00 = gy * gx, w01 = gy * fx, w10 = fy * gx, w11 = fy * fx;
+        const int64_t face = (int64_t)t.face * td->Ht * td->Wt;
+        const float *t00 = tex + (face + (int64_t)t.y[0] * td->Wt + t.x[0]) * Ct;
+        const float *t01 = tex + (face + (int64_t)t.y[0] * td->Wt + t.x[1]) * Ct;
+        const float *t10 = tex + (face + (int64_t)t.y[1] * td->Wt + t.x[0]) * Ct;
+        const float *t11 = tex + (face + (int64_t)t.y[1] * td->Wt + t.x[1]) * Ct;
+        for (int c = 0; c < Ct; c++) {
+            float s = w00 * t00[c];
+            s = s + w01 * t01[c];
+            s = s + w10 * t10[c];
+            y[c] = s + w11 * t11[c];
+        }
+    }
+    return 0;
+}

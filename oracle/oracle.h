@@ -43,6 +43,8 @@ int orc_interpolate(const double *attr, int Ba, int Va, int C, const int32_t *at
 int orc_interpolate_bwd(const double *attr, int Ba, int Va, int C, const int32_t *attr_tris,
                         int T, const int32_t *tri_id, const double *bary, int B, int K, int H,
                         int W, const double *grad_out, double *grad_attr, double *grad_bary);
+int orc_texture_f32(const float *tex, const orc_tex_desc *td, const float *coord,
+                    const int32_t *tri_id, int64_t N, float *out);
 int orc_texture(const double *tex, const orc_tex_desc *td, const float *coord,
                 const int32_t *tri_id, int64_t N, double *out);
 int orc_texture_bwd_coord(const double *tex, const orc_tex_desc *td, const float *coord,
