@@ -131,19 +131,26 @@ def resolve(pos_clip, tris, tri_id, hard, snap=True, cull=0):
     return bary, dist
 
 
-def rasterize_bwd(pos_clip, tris, tri_id, hard, grad_bary, grad_dist=None, snap=True, cull=0):
+def rasterize_bwd(pos_clip, tris, tri_id, hard, grad_bary, grad_dist=None, snap=True, cull=0,
+                  image=None, window=None):
+    """Gradient of (bary, dist) w.r.t. pos_clip [B,V,4].  With `window` =
+    (x0, y0, w, h) of an `image` = (H, W), the per-pixel arrays hold that
+    window's pixels (as rasterize_window gives them)."""
     pc = _f32(pos_clip)
     if pc.ndim == 2:
         pc = pc[None]
     B, V, _ = pc.shape
     t = _i32(tris)
     tid = _i32(tri_id)
-    _, K, H, W = tid.shape
+    _, K, h, w = tid.shape
+    H, W = (h, w) if image is None else (int(image[0]), int(image[1]))
+    x0, y0, ww, wh = (0, 0, w, h) if window is None else (int(v) for v in window)
+    assert (ww, wh) == (w, h), "window size differs from the arrays"
     gp = np.empty((B, V, 4), np.float64)
     gd = _f64(grad_dist) if grad_dist is not None else None
-    f = lib().orc_rasterize_bwd
-    f.argtypes = [C.c_void_p, C.c_void_p] + [C.c_int] * 8 + [C.c_void_p] * 5
-    _check(f(_p(pc), _p(t), B, V, t.shape[0], H, W, K, cull, int(snap), _p(tid),
+    f = lib().orc_rasterize_bwd_window
+    f.argtypes = [C.c_void_p, C.c_void_p] + [C.c_int] * 12 + [C.c_void_p] * 5
+    _check(f(_p(pc), _p(t), B, V, t.shape[0], H, W, K, cull, int(snap), x0, y0, ww, wh, _p(tid),
              _p(_u8(hard)), _p(_f64(grad_bary)), _p(gd), _p(gp)), "rasterize_bwd")
     return gp
 

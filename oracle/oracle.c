@@ -430,19 +430,23 @@ int orc_resolve(const float *pos_clip, const int32_t *tris, int B, int V, int T,
  * vertices only through the barycentrics and the signed distance, which are
  * differentiable functions of the projected vertices.  Snapping is treated as
  * the identity (straight-through), with values taken at the snapped point. */
-int orc_rasterize_bwd(const float *pos_clip, const int32_t *tris, int B, int V, int T,
-                      int H, int W, int K, int cull, int snap,
-                      const int32_t *tri_id, const uint8_t *hard,
-                      const double *grad_bary, const double *grad_dist, double *grad_pos)
+/* The pixels of window (wx0, wy0, ww, wh) of an H x W image: tri_id, hard,
+ * grad_bary and grad_dist are [B,K,wh,ww]; the whole image is the window
+ * (0, 0, W, H). */
+int orc_rasterize_bwd_window(const float *pos_clip, const int32_t *tris, int B, int V, int T,
+                             int H, int W, int K, int cull, int snap, int wx0, int wy0, int ww, int wh,
+                             const int32_t *tri_id, const uint8_t *hard,
+                             const double *grad_bary, const double *grad_dist, double *grad_pos)
 {
+    if (wx0 < 0 || wy0 < 0 || ww <= 0 || wh <= 0 || wx0 + ww > W || wy0 + wh > H) return -1;
     memset(grad_pos, 0, sizeof(double) * (size_t)B * V * 4);
     for (int b = 0; b < B; b++) {
         const float *pc = pos_clip + (int64_t)b * V * 4;
         double *gp = grad_pos + (int64_t)b * V * 4;
         for (int k = 0; k < K; k++)
-            for (int y = 0; y < H; y++)
-                for (int x = 0; x < W; x++) {
-                    int64_t o = (((int64_t)b * K + k) * H + y) * W + x;
+            for (int y = wy0; y < wy0 + wh; y++)
+                for (int x = wx0; x < wx0 + ww; x++) {
+                    int64_t o = (((int64_t)b * K + k) * wh + (y - wy0)) * ww + (x - wx0);
                     int32_t t = tri_id[o];
                     if (t < 0 || t >= T) continue;
                     otri s = setup_tri(pc, tris + 3 * (int64_t)t, H, W, cull);
@@ -505,6 +509,15 @@ int orc_rasterize_bwd(const float *pos_clip, const int32_t *tris, int B, int V, 
                 }
     }
     return 0;
+}
+
+int orc_rasterize_bwd(const float *pos_clip, const int32_t *tris, int B, int V, int T,
+                      int H, int W, int K, int cull, int snap,
+                      const int32_t *tri_id, const uint8_t *hard,
+                      const double *grad_bary, const double *grad_dist, double *grad_pos)
+{
+    return orc_rasterize_bwd_window(pos_clip, tris, B, V, T, H, W, K, cull, snap, 0, 0, W, H,
+                                    tri_id, hard, grad_bary, grad_dist, grad_pos);
 }
 
 /* ------------------------------------------------------------------------ */

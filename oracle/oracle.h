@@ -33,6 +33,10 @@ int orc_rasterize_window(const float *pos_clip, const int32_t *tris, int B, int 
 int orc_resolve(const float *pos_clip, const int32_t *tris, int B, int V, int T,
                 int H, int W, int K, int cull, int snap,
                 const int32_t *tri_id, const uint8_t *hard, double *bary, double *dist);
+int orc_rasterize_bwd_window(const float *pos_clip, const int32_t *tris, int B, int V, int T,
+                             int H, int W, int K, int cull, int snap, int wx0, int wy0, int ww, int wh,
+                             const int32_t *tri_id, const uint8_t *hard,
+                             const double *grad_bary, const double *grad_dist, double *grad_pos);
 int orc_rasterize_bwd(const float *pos_clip, const int32_t *tris, int B, int V, int T,
                       int H, int W, int K, int cull, int snap,
                       const int32_t *tri_id, const uint8_t *hard,

@@ -2,10 +2,15 @@
 as the GPU step (§3.4.1: transform and vertex normals, rasterization,
 interpolation, texture sampling, deferred shading, HardSoftRas blend, L2
 loss, then the adjoints in reverse), composed from the oracle's own
-functions in double precision.  Two values that feed discrete decisions are
-computed in single precision with the kernel's operation order (the clip
-coordinates, which are snapped, and the texture coordinates, whose texel and
-inverse-UV cell are selected), so that those decisions coincide."""
+functions in double precision.
+
+Values that feed discrete decisions are taken in single precision with the
+kernel's operation order, so that those decisions coincide: the clip
+coordinates (snapped), the texture coordinates (texel and inverse-UV cell),
+and the G-buffer rows the shading starts from (interpolated normal, position
+and tangent, and the normal-map sample), whose shading normal selects the
+environment map's cube face, texels and cell and the side of every
+max(0, .) kink.  The shading itself is double precision on those values."""
 from __future__ import annotations
 
 import numpy as np
@@ -28,7 +33,11 @@ def _params(scene, target):
     return pos, color, tex
 
 
-def forward(scene, views=None, target=False):
+def forward(scene, views=None, target=False, window=None):
+    """Forward of the scene's views.  window = (x0, y0, w, h): only the
+    pixels of that rectangle of each H x W image (every triangle considered;
+    the edge mask is exact where its boundary test and dilation stay inside
+    the window)."""
     sl = slice(None) if views is None else views
     mvp = scene.mvp[sl].astype(np.float32)
     eye = scene.eyes[sl].astype(np.float64)
@@ -47,16 +56,24 @@ def forward(scene, views=None, target=False):
         extra = np.asarray(scene.extra["tangent"], np.float64)
     vattr = np.concatenate([n, st["pos"]] + ([extra] if extra is not None else []), 1)
     pc = O.transform_f32(pos32, mvp)
-    tid, hard, bary, dist = O.rasterize(pc, tris, H, W, K=K, r=r)
+    if window is None:
+        tid, hard, bary, dist = O.rasterize(pc, tris, H, W, K=K, r=r)
+    else:
+        tid, hard, bary, dist = O.rasterize_window(pc, tris, H, W, window, K=K, r=r)
     gb = O.interpolate(vattr, tris, tid, bary)
-    st.update(vattr=vattr, pc=pc, tid=tid, hard=hard, bary=bary, dist=dist if r > 0 else None, gbuf=gb)
-    nrm = gb[..., 0:3]
-    p = gb[..., 3:6]
+    # the shading's inputs: the per-vertex rows rounded once to float, then
+    # interpolated in float (decision values, see the module docstring)
+    b32 = bary.astype(np.float32)
+    gs = O.interpolate_f32(vattr.astype(np.float32), tris, tid, b32).astype(np.float64)
+    st.update(vattr=vattr, pc=pc, tid=tid, hard=hard, bary=bary, dist=dist if r > 0 else None, gbuf=gb,
+              gshade=gs, image=(H, W), window=window)
+    nrm = gs[..., 0:3]
+    p = gs[..., 3:6]
     if mode == O.SHADE_LAMBERT:
-        albedo = gb[..., 6:9]
+        albedo = gs[..., 6:9]
         shade_n = nrm
     else:
-        uv = O.interpolate_f32(scene.uv, scene.uv_tris, tid, bary.astype(np.float32))
+        uv = O.interpolate_f32(scene.uv, scene.uv_tris, tid, b32)
         wu, wv = scene.extra.get("wrap", (O.WRAP_REPEAT, O.WRAP_CLAMP))
         samp = O.texture(tex, uv, tid, wrap_u=wu, wrap_v=wv)
         st.update(uv=uv, samp=samp)
@@ -64,7 +81,9 @@ def forward(scene, views=None, target=False):
         shade_n = nrm
     env_s = None
     if mode == O.SHADE_PHONG_ENV:
-        shade_n = O.normal_map(nrm, gb[..., 6:9], samp[..., 4:7], tid)
+        m32 = O.texture_f32(tex, uv, tid, wrap_u=wu, wrap_v=wv)[..., 4:7].astype(np.float64)
+        shade_n = O.normal_map(nrm, gs[..., 6:9], m32, tid)
+        st.update(nmap_s=m32)
         d = O.reflect(shade_n, p, eye, tid)
         env_s = O.texture(scene.env, d.astype(np.float32), tid, kind=O.TEX_CUBE)
         st.update(shade_n=shade_n, dir=d, env_s=env_s)
@@ -74,19 +93,27 @@ def forward(scene, views=None, target=False):
     # scene may choose the anti-aliasing or SoftRas-like settings instead
     blend = {"hsr": O.BLEND_HSR, "aa": O.BLEND_AA, "softras": O.BLEND_SOFTRAS,
              "hard": O.BLEND_HARD}[scene.extra.get("blend", "hsr" if r > 0 else "hard")]
-    oc, os_, E = O.softras(col, st["dist"], tid, sigma, r, blend)
+    # the dilation radius ceil(delta * width) - 1 is set by the image width
+    delta = r if window is None else r * W / window[2]
+    oc, os_, E = O.softras(col, st["dist"], tid, sigma, delta, blend)
     st.update(layer_color=col, albedo=albedo, color=oc, sil=os_, E=E, sigma=sigma)
     st["rgba"] = np.concatenate([oc, os_[..., None]], -1)
     return st
 
 
-def backward(scene, st, target_rgba):
+def backward(scene, st, target_rgba=None, grad_rgba=None):
+    """Adjoint of the L2 loss against target_rgba, or, with grad_rgba, of a
+    given image gradient [B,H,W,4] (colour, silhouette)."""
     mode = st["mode"]
     tid = st["tid"]
     tris = scene.tris
-    L, g_c, g_s = O.loss_l2(st["color"], st["sil"], target_rgba)
+    if grad_rgba is None:
+        L, g_c, g_s = O.loss_l2(st["color"], st["sil"], target_rgba)
+    else:
+        g = np.asarray(grad_rgba, np.float64)
+        L, g_c, g_s = None, g[..., 0:3], g[..., 3]
     gl, gd = O.softras_bwd(st["layer_color"], st["dist"], tid, st["sigma"], st["E"], g_c, g_s)
-    gb = st["gbuf"]
+    gb = st["gshade"]
     nrm, p = gb[..., 0:3], gb[..., 3:6]
     eye = st["eye"]
     g_gbuf = np.zeros_like(gb)
@@ -108,7 +135,7 @@ def backward(scene, st, target_rgba):
                                        tid.reshape((-1,) + tid.shape[2:]),
                                        ge.reshape((-1,) + ge.shape[2:]), kind=O.TEX_CUBE)
         gnp2, gp2 = O.reflect_bwd(st["shade_n"], p, eye, tid, gdir)
-        gn, gt, gm = O.normal_map_bwd(nrm, gb[..., 6:9], st["samp"][..., 4:7], tid, gnp + gnp2)
+        gn, gt, gm = O.normal_map_bwd(nrm, gb[..., 6:9], st["nmap_s"], tid, gnp + gnp2)
         g_gbuf[..., 0:3] = gn
         g_gbuf[..., 3:6] = gp + gp2
         g_gbuf[..., 6:9] = gt
@@ -124,7 +151,9 @@ def backward(scene, st, target_rgba):
         _, g_bary_uv = O.interpolate_bwd(scene.uv, scene.uv_tris, tid, st["bary"], g_uv)
     g_vattr, g_bary = O.interpolate_bwd(st["vattr"], tris, tid, st["bary"], g_gbuf)
     g_bary = g_bary + g_bary_uv
-    g_clip = O.rasterize_bwd(st["pc"], tris, tid, st["hard"], g_bary, O_grad_dist(gd, st))
+    g_clip = O.rasterize_bwd(st["pc"], tris, tid, st["hard"], g_bary, O_grad_dist(gd, st),
+                             image=st["image"], window=st["window"])
+    out["clip"] = g_clip
     g_pos = O.transform_bwd(st["mvp"], g_clip)
     g_pos += O.vertex_normals_bwd(st["pos"], tris, g_vattr[:, 0:3]) + g_vattr[:, 3:6]
     out["pos"] = g_pos

@@ -307,54 +307,83 @@ extern "C" int dressi_vertex_attrs_bwd(dressi_ctx *ctx, const float *pos, const 
 // ---------------------------------------------------------------------------
 // deferred shading
 // ---------------------------------------------------------------------------
-__constant__ float c_light[3] = {0.408248290463863f, 0.408248290463863f, 0.816496580927726f};
+// The shading chain runs in double from the float G-buffer values and is
+// rounded once at the outputs.  Its results feed discrete decisions: the
+// reflection direction selects a cube face, texels and an inverse-UV cell,
+// and n.l and r.v pick a side of the max(0, .) kinks.  Computed in double
+// from the same float inputs, those choices do not depend on the order of
+// the arithmetic, so they coincide with a double-precision reference.
+__constant__ double c_light[3] = {0.40824829046386302, 0.40824829046386302, 0.81649658092772603};
+
+struct d3 {
+    double x, y, z;
+};
+__device__ __forceinline__ d3 ldd3(const float *p) { return d3{p[0], p[1], p[2]}; }
+__device__ __forceinline__ d3 operator+(d3 a, d3 b) { return d3{a.x + b.x, a.y + b.y, a.z + b.z}; }
+__device__ __forceinline__ d3 operator-(d3 a, d3 b) { return d3{a.x - b.x, a.y - b.y, a.z - b.z}; }
+__device__ __forceinline__ d3 operator*(double s, d3 a) { return d3{s * a.x, s * a.y, s * a.z}; }
+__device__ __forceinline__ double dotd(d3 a, d3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ d3 crossd(d3 a, d3 b) {
+    return d3{a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+__device__ __forceinline__ d3 normalized(d3 a) {
+    const double l = sqrt(dotd(a, a));
+    return l > 0.0 ? (1.0 / l) * a : d3{0.0, 0.0, 0.0};
+}
+// gradient of normalize(a): (g - (g.n) n) / |a|
+__device__ __forceinline__ d3 normalized_bwd(d3 a, d3 g) {
+    const double l = sqrt(dotd(a, a));
+    if (!(l > 0.0)) return d3{0.0, 0.0, 0.0};
+    const d3 n = (1.0 / l) * a;
+    return (1.0 / l) * (g - dotd(g, n) * n);
+}
 
 struct ShadeState {
-    float3 nin, nh, t, tp, th, bh, m, u, np;   // normal-map chain (np = shading normal)
-    float3 vv, vh;                              // view vector and its direction
-    float ndl, rv, spec, base, kd;
-    float3 r;
-    float a[4];
-    float3 e;
+    d3 nin, nh, t, tp, th, bh, m, u, np;   // normal-map chain (np = shading normal)
+    d3 vv, vh;                              // view vector and its direction
+    double ndl, rv, spec, base, kd;
+    d3 r;
+    double a[4];
+    d3 e;
 };
 
 __device__ __forceinline__ void shade_forward(int mode, const dressi_frag_in &in, const float *eye,
                                               int64_t i, bool need_view, ShadeState &s) {
-    s.nin = ld3(in.normal + i * in.normal_stride);
-    s.nh = normalize3(s.nin);
+    s.nin = ldd3(in.normal + i * in.normal_stride);
+    s.nh = normalized(s.nin);
     s.np = s.nh;
     if (in.tangent && in.nmap) {
-        s.t = ld3(in.tangent + i * in.tangent_stride);
-        s.m = ld3(in.nmap + i * in.nmap_stride);
-        s.tp = s.t - dot3(s.t, s.nh) * s.nh;
-        s.th = normalize3(s.tp);
-        s.bh = cross3(s.nh, s.th);
+        s.t = ldd3(in.tangent + i * in.tangent_stride);
+        s.m = ldd3(in.nmap + i * in.nmap_stride);
+        s.tp = s.t - dotd(s.t, s.nh) * s.nh;
+        s.th = normalized(s.tp);
+        s.bh = crossd(s.nh, s.th);
         s.u = s.m.x * s.th + s.m.y * s.bh + s.m.z * s.nh;
-        s.np = normalize3(s.u);
+        s.np = normalized(s.u);
     }
     if (need_view) {
-        s.vv = ld3(eye) - ld3(in.pos + i * in.pos_stride);
-        s.vh = normalize3(s.vv);
+        s.vv = ldd3(eye) - ldd3(in.pos + i * in.pos_stride);
+        s.vh = normalized(s.vv);
     }
-    const float3 L = make_float3(c_light[0], c_light[1], c_light[2]);
-    s.ndl = dot3(s.np, L);
-    s.kd = mode == DRESSI_SHADE_LAMBERT ? 0.9f : 0.8f;
-    s.base = 0.1f + s.kd * fmaxf(s.ndl, 0.0f);
-    s.spec = 0.0f;
-    s.rv = 0.0f;
+    const d3 L{c_light[0], c_light[1], c_light[2]};
+    s.ndl = dotd(s.np, L);
+    s.kd = mode == DRESSI_SHADE_LAMBERT ? 0.9 : 0.8;
+    s.base = 0.1 + s.kd * fmax(s.ndl, 0.0);
+    s.spec = 0.0;
+    s.rv = 0.0;
     if (mode != DRESSI_SHADE_LAMBERT) {
-        s.r = (2.0f * s.ndl) * s.np - L;
-        s.rv = dot3(s.r, s.vh);
-        if (s.rv > 0.0f) {
-            float r2 = s.rv * s.rv, r4 = r2 * r2, r8 = r4 * r4, r16 = r8 * r8;
+        s.r = (2.0 * s.ndl) * s.np - L;
+        s.rv = dotd(s.r, s.vh);
+        if (s.rv > 0.0) {
+            const double r2 = s.rv * s.rv, r4 = r2 * r2, r8 = r4 * r4, r16 = r8 * r8;
             s.spec = r16 * r16;
         }
     }
     const float *ap = in.albedo + i * in.albedo_stride;
     s.a[0] = ap[0]; s.a[1] = ap[1]; s.a[2] = ap[2];
-    s.a[3] = in.albedo_channels > 3 ? ap[3] : 0.0f;
-    s.e = make_float3(0.0f, 0.0f, 0.0f);
-    if (mode == DRESSI_SHADE_PHONG_ENV && in.env) s.e = ld3(in.env + i * in.env_stride);
+    s.a[3] = in.albedo_channels > 3 ? ap[3] : 0.0;
+    s.e = d3{0.0, 0.0, 0.0};
+    if (mode == DRESSI_SHADE_PHONG_ENV && in.env) s.e = ldd3(in.env + i * in.env_stride);
 }
 
 __global__ void k_shade(int mode, dressi_frag_in in, const float *__restrict__ eye,
@@ -371,22 +400,22 @@ __global__ void k_shade(int mode, dressi_frag_in in, const float *__restrict__ e
     ShadeState s;
     shade_forward(mode, in, eye + 3 * e, i, mode != DRESSI_SHADE_LAMBERT || dir != nullptr, s);
     if (dir) {
-        float3 d = (2.0f * dot3(s.np, s.vh)) * s.np - s.vh;
-        dir[3 * i] = d.x; dir[3 * i + 1] = d.y; dir[3 * i + 2] = d.z;
+        const d3 d = (2.0 * dotd(s.np, s.vh)) * s.np - s.vh;
+        dir[3 * i] = (float)d.x; dir[3 * i + 1] = (float)d.y; dir[3 * i + 2] = (float)d.z;
     }
     if (color) {
-        float add = 0.0f;
-        if (mode != DRESSI_SHADE_LAMBERT) add = 0.2f * s.a[3] * s.spec;
-        float env = mode == DRESSI_SHADE_PHONG_ENV ? 0.5f * s.a[3] : 0.0f;
-        color[3 * i] = s.a[0] * s.base + add + env * s.e.x;
-        color[3 * i + 1] = s.a[1] * s.base + add + env * s.e.y;
-        color[3 * i + 2] = s.a[2] * s.base + add + env * s.e.z;
+        double add = 0.0;
+        if (mode != DRESSI_SHADE_LAMBERT) add = 0.2 * s.a[3] * s.spec;
+        const double env = mode == DRESSI_SHADE_PHONG_ENV ? 0.5 * s.a[3] : 0.0;
+        color[3 * i] = (float)(s.a[0] * s.base + add + env * s.e.x);
+        color[3 * i + 1] = (float)(s.a[1] * s.base + add + env * s.e.y);
+        color[3 * i + 2] = (float)(s.a[2] * s.base + add + env * s.e.z);
     }
 }
 
-__device__ __forceinline__ void st3(float *p, int64_t i, int stride, float3 v) {
+__device__ __forceinline__ void st3(float *p, int64_t i, int stride, d3 v) {
     float *q = p + i * stride;
-    q[0] = v.x; q[1] = v.y; q[2] = v.z;
+    q[0] = (float)v.x; q[1] = (float)v.y; q[2] = (float)v.z;
 }
 
 __global__ void k_shade_bwd(int mode, dressi_frag_in in, const float *__restrict__ eye,
@@ -395,7 +424,7 @@ __global__ void k_shade_bwd(int mode, dressi_frag_in in, const float *__restrict
                             dressi_frag_grad gr) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
-    const float3 Z = make_float3(0.0f, 0.0f, 0.0f);
+    const d3 Z{0.0, 0.0, 0.0};
     if (tri_id[i] < 0) {
         if (gr.normal) st3(gr.normal, i, gr.normal_stride, Z);
         if (gr.pos) st3(gr.pos, i, gr.pos_stride, Z);
@@ -412,56 +441,56 @@ __global__ void k_shade_bwd(int mode, dressi_frag_in in, const float *__restrict
     bool need_geo = gr.normal || gr.pos || gr.tangent || gr.nmap;
     ShadeState s;
     shade_forward(mode, in, eye + 3 * e, i, mode != DRESSI_SHADE_LAMBERT || grad_dir != nullptr, s);
-    float3 g = grad_color ? ld3(grad_color + 3 * i) : Z;
-    float gsum = g.x + g.y + g.z;
+    const d3 g = grad_color ? ldd3(grad_color + 3 * i) : Z;
+    const double gsum = g.x + g.y + g.z;
     if (gr.albedo) {
         float *q = gr.albedo + i * gr.albedo_stride;
-        q[0] = g.x * s.base; q[1] = g.y * s.base; q[2] = g.z * s.base;
+        q[0] = (float)(g.x * s.base); q[1] = (float)(g.y * s.base); q[2] = (float)(g.z * s.base);
         if (in.albedo_channels > 3) {
-            float ga = 0.0f;
-            if (mode != DRESSI_SHADE_LAMBERT) ga += 0.2f * s.spec * gsum;
-            if (mode == DRESSI_SHADE_PHONG_ENV) ga += 0.5f * dot3(g, s.e);
-            q[3] = ga;
+            double ga = 0.0;
+            if (mode != DRESSI_SHADE_LAMBERT) ga += 0.2 * s.spec * gsum;
+            if (mode == DRESSI_SHADE_PHONG_ENV) ga += 0.5 * dotd(g, s.e);
+            q[3] = (float)ga;
         }
     }
-    if (gr.env) st3(gr.env, i, gr.env_stride, mode == DRESSI_SHADE_PHONG_ENV ? (0.5f * s.a[3]) * g : Z);
+    if (gr.env) st3(gr.env, i, gr.env_stride, mode == DRESSI_SHADE_PHONG_ENV ? (0.5 * s.a[3]) * g : Z);
     if (!need_geo) return;
-    const float3 L = make_float3(c_light[0], c_light[1], c_light[2]);
-    float3 gnp = Z, gvh = Z;
-    float gdot = g.x * s.a[0] + g.y * s.a[1] + g.z * s.a[2];
-    if (s.ndl > 0.0f) gnp = (s.kd * gdot) * L;
-    if (mode != DRESSI_SHADE_LAMBERT && s.rv > 0.0f) {
-        float r2 = s.rv * s.rv, r4 = r2 * r2, r8 = r4 * r4, r16 = r8 * r8;
-        float r31 = r16 * r8 * r4 * r2 * s.rv;
-        float grv = 0.2f * s.a[3] * gsum * 32.0f * r31;
-        float3 gr_ = grv * s.vh;
+    const d3 L{c_light[0], c_light[1], c_light[2]};
+    d3 gnp = Z, gvh = Z;
+    const double gdot = g.x * s.a[0] + g.y * s.a[1] + g.z * s.a[2];
+    if (s.ndl > 0.0) gnp = (s.kd * gdot) * L;
+    if (mode != DRESSI_SHADE_LAMBERT && s.rv > 0.0) {
+        const double r2 = s.rv * s.rv, r4 = r2 * r2, r8 = r4 * r4, r16 = r8 * r8;
+        const double r31 = r16 * r8 * r4 * r2 * s.rv;
+        const double grv = 0.2 * s.a[3] * gsum * 32.0 * r31;
+        const d3 gr_ = grv * s.vh;
         gvh = gvh + grv * s.r;
-        gnp = gnp + (2.0f * s.ndl) * gr_ + (2.0f * dot3(gr_, s.np)) * L;
+        gnp = gnp + (2.0 * s.ndl) * gr_ + (2.0 * dotd(gr_, s.np)) * L;
     }
     if (grad_dir) {
-        float3 gd = ld3(grad_dir + 3 * i);
-        float d = dot3(s.np, s.vh), gdn = dot3(gd, s.np);
-        gnp = gnp + (2.0f * d) * gd + (2.0f * gdn) * s.vh;
-        gvh = gvh + (2.0f * gdn) * s.np - gd;
+        const d3 gd = ldd3(grad_dir + 3 * i);
+        const double d = dotd(s.np, s.vh), gdn = dotd(gd, s.np);
+        gnp = gnp + (2.0 * d) * gd + (2.0 * gdn) * s.vh;
+        gvh = gvh + (2.0 * gdn) * s.np - gd;
     }
     if (gr.pos) {
-        float3 gvv = (mode != DRESSI_SHADE_LAMBERT || grad_dir) ? normalize3_bwd(s.vv, gvh) : Z;
-        st3(gr.pos, i, gr.pos_stride, make_float3(-gvv.x, -gvv.y, -gvv.z));
+        const d3 gvv = (mode != DRESSI_SHADE_LAMBERT || grad_dir) ? normalized_bwd(s.vv, gvh) : Z;
+        st3(gr.pos, i, gr.pos_stride, d3{-gvv.x, -gvv.y, -gvv.z});
     }
     if (in.tangent && in.nmap) {
-        float3 gu = normalize3_bwd(s.u, gnp);
-        if (gr.nmap) st3(gr.nmap, i, gr.nmap_stride, make_float3(dot3(gu, s.th), dot3(gu, s.bh), dot3(gu, s.nh)));
-        float3 gth = s.m.x * gu, gbh = s.m.y * gu, gnh = s.m.z * gu;
-        gnh = gnh + cross3(s.th, gbh);
-        gth = gth + cross3(gbh, s.nh);
-        float3 gtp = normalize3_bwd(s.tp, gth);
-        float d = dot3(s.t, s.nh);
-        float gd = -dot3(gtp, s.nh);
+        const d3 gu = normalized_bwd(s.u, gnp);
+        if (gr.nmap) st3(gr.nmap, i, gr.nmap_stride, d3{dotd(gu, s.th), dotd(gu, s.bh), dotd(gu, s.nh)});
+        d3 gth = s.m.x * gu, gbh = s.m.y * gu, gnh = s.m.z * gu;
+        gnh = gnh + crossd(s.th, gbh);
+        gth = gth + crossd(gbh, s.nh);
+        const d3 gtp = normalized_bwd(s.tp, gth);
+        const double d = dotd(s.t, s.nh);
+        const double gd = -dotd(gtp, s.nh);
         if (gr.tangent) st3(gr.tangent, i, gr.tangent_stride, gtp + gd * s.nh);
         gnh = gnh + (-d) * gtp + gd * s.t;
-        if (gr.normal) st3(gr.normal, i, gr.normal_stride, normalize3_bwd(s.nin, gnh));
+        if (gr.normal) st3(gr.normal, i, gr.normal_stride, normalized_bwd(s.nin, gnh));
     } else {
-        if (gr.normal) st3(gr.normal, i, gr.normal_stride, normalize3_bwd(s.nin, gnp));
+        if (gr.normal) st3(gr.normal, i, gr.normal_stride, normalized_bwd(s.nin, gnp));
         if (gr.tangent) st3(gr.tangent, i, gr.tangent_stride, Z);
         if (gr.nmap) st3(gr.nmap, i, gr.nmap_stride, Z);
     }

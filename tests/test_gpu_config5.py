@@ -83,21 +83,9 @@ def test_config5_raster_windows(cfg5, step5, clip5):
 
 def _oracle_window_image(cfg5, clip, v, region):
     """The oracle's forward (Phong, HardSoftRas) on one view's region."""
-    x0, y0, w, h = region
-    H, W, K, r = cfg5.H, cfg5.W, cfg5.K, cfg5.r
-    tid, hard, bary, dist = oracle.rasterize_window(clip[v:v + 1], cfg5.tris, H, W, region, K=K, r=r)
-    n = oracle.vertex_normals(cfg5.pos, cfg5.tris)
-    vattr = np.concatenate([n, cfg5.pos.astype(np.float64)], 1)
-    g = oracle.interpolate(vattr, cfg5.tris, tid, bary)
-    uv = oracle.interpolate_f32(cfg5.uv, cfg5.uv_tris, tid, bary.astype(np.float32))
-    wu, wv = cfg5.extra["wrap"]
-    alb = oracle.texture(cfg5.tex, uv, tid, wrap_u=wu, wrap_v=wv)
-    col = oracle.shade(oracle.SHADE_PHONG, g[..., 0:3], g[..., 3:6], alb, None, cfg5.eyes[v:v + 1], tid)
-    sigma = r / 7.0
-    # the edge mask's dilation radius is set by the full image width
-    delta = r * W / w
-    oc, osil, E = oracle.softras(col, dist, tid, sigma, delta, oracle.BLEND_HSR)
-    return oc, osil, E
+    from oracle import step as ostep
+    o = ostep.forward(cfg5, views=slice(v, v + 1), window=region)
+    return o["color"], o["sil"], o["E"]
 
 
 def test_config5_image_windows(cfg5, step5, clip5):
@@ -135,3 +123,48 @@ def test_config5_step_properties(cfg5, step5):
     torch.cuda.synchronize()
     for k, v in step5.grads().items():
         assert np.array_equal(host(v), g[k]), f"{k} not bitwise reproducible"
+
+
+def _bottom_band(clip, v, H, W, r, rows=24):
+    """A full-width band from `rows` rows above the lowest projected vertex of
+    view v to the bottom of the image, and the oracle's window: the band plus
+    the rows above it that the edge mask's boundary test and dilation read.
+    Inverse-UV winners are the largest pixel indices of a cell, and every
+    pixel of such a band has a larger index than every pixel outside it, so
+    a cell reached from the band keeps the same winner in the window and in
+    the whole image."""
+    y = (1.0 - clip[v, :, 1] / clip[v, :, 3]) * (H / 2.0)
+    y0 = int(math.ceil(float(y.max()))) - rows
+    top = y0 - (math.ceil(r * W) - 1 + 2)
+    return y0, (0, top, W, H - top)
+
+
+@pytest.mark.timeout(600)
+def test_config5_gradients_bottom_band(cfg5, step5, clip5):
+    """Full-size backward at config 5 with an image gradient that is zero
+    except in a bottom band of one view: the clip-space, world-position and
+    texture gradients against the oracle's backward over that band's window
+    (its window rasterizer and the adjoints of every stage), at rel 1e-4 in
+    norm and element-wise."""
+    from oracle import step as ostep
+    from test_gpu_parity import assert_grad_close
+    H, W, r = cfg5.H, cfg5.W, cfg5.r
+    for v in (2, 5):
+        y0, win = _bottom_band(clip5, v, H, W, r)
+        top = win[1]
+        print(f"config 5 view {v}: band rows {y0}..{H}, window {win}", flush=True)
+        G = np.zeros((cfg5.mvp.shape[0], H, W, 4), np.float32)
+        G[v, y0:] = np.random.default_rng(50 + v).standard_normal((H - y0, W, 4))
+        Gt = torch.from_numpy(G).cuda()
+        step5.g_color.copy_(Gt[..., :3])
+        step5.g_sil.copy_(Gt[..., 3])
+        step5.backward()
+        torch.cuda.synchronize()
+        o = ostep.forward(cfg5, views=slice(v, v + 1), window=win)
+        assert (o["tid"][0, 0, y0 - top:] >= 0).sum() > 1000, "the band should hold geometry"
+        og = ostep.backward(cfg5, o, grad_rgba=G[v:v + 1, top:].astype(np.float64))
+        gclip = host(step5.g_clip)
+        assert not gclip[np.arange(gclip.shape[0]) != v].any(), "views without gradient must give zero"
+        assert_grad_close(gclip[v], og["clip"][0], what=f"view {v} grad clip")
+        assert_grad_close(host(step5.g_pos), og["pos"], what=f"view {v} grad pos")
+        assert_grad_close(host(step5.g_tex), og["tex"], what=f"view {v} grad texture")

@@ -359,3 +359,26 @@ def test_window_equals_crop_of_full_image():
         part = oracle.rasterize_window(pc, s.tris, 128, 128, win, K=3, r=0.05)
         for a, b in zip(full, part):
             assert np.array_equal(a[:, :, y0:y0 + h, x0:x0 + w], b)
+
+
+def test_window_adjoint_equals_full_adjoint_with_gradient_only_there():
+    """The window form of the rasterization adjoint (used for sampled checks
+    of large images) equals the full-image adjoint whose incoming gradients
+    are zero outside the window."""
+    s = scenes.config1()
+    pc = oracle.transform_f32(s.pos, s.mvp)
+    H = W = 96
+    tid, hard, _, _ = oracle.rasterize(pc, s.tris, H, W, K=3, r=0.05)
+    rng = np.random.default_rng(5)
+    gb = rng.standard_normal(tid.shape + (2,))
+    gd = rng.standard_normal(tid.shape)
+    for win in [(0, 0, W, H), (10, 40, 60, 56), (0, 70, W, 26), (47, 3, 1, 50)]:
+        x0, y0, w, h = win
+        mask = np.zeros(tid.shape, bool)
+        mask[:, :, y0:y0 + h, x0:x0 + w] = True
+        full = oracle.rasterize_bwd(pc, s.tris, tid, hard, gb * mask[..., None], gd * mask)
+        cut = lambda a: np.ascontiguousarray(a[:, :, y0:y0 + h, x0:x0 + w])
+        part = oracle.rasterize_bwd(pc, s.tris, cut(tid), cut(hard), cut(gb), cut(gd),
+                                    image=(H, W), window=win)
+        assert np.abs(full).max() > 0
+        assert np.allclose(part, full, rtol=1e-12, atol=1e-12 * np.abs(full).max())
