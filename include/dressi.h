@@ -78,7 +78,12 @@ int dressi_create(dressi_ctx **ctx, int device);
 int dressi_destroy(dressi_ctx *ctx);
 const char *dressi_last_error(const dressi_ctx *ctx);
 /* Grow scratch to at least `bytes` and the tile-bin capacity to at least
- * `bin_entries` (pass 0 to leave either unchanged).  Synchronises the device. */
+ * `bin_entries` (pass 0 to leave either unchanged).  Synchronises the device.
+ * Scratch grows (here, or in an eager call that needs more) by allocating a
+ * larger arena; the old one is retired, not freed, because a graph captured
+ * before the growth still uses its addresses.  Retired arenas are freed by
+ * dressi_destroy, so a captured graph stays valid until then; reserve the
+ * largest shapes first to keep a single arena. */
 int dressi_reserve(dressi_ctx *ctx, size_t bytes, int64_t bin_entries);
 /* Bytes of scratch the given call shapes need (for dressi_reserve before a
  * graph capture).  Pass the largest shapes of the step. */

@@ -223,6 +223,27 @@ def _need(t, dtype, name):
     return t
 
 
+def _checked_raster(ctx, call, what):
+    """Runs a rasterization, then reads the device's bin-overflow status (a
+    host synchronisation; skipped while the stream is being captured).  On
+    overflow the bins grow to the reported need and the call runs once more;
+    a second overflow raises.  Outputs are never returned from an overflowed
+    call."""
+    ctx.check(call(), what)
+    if torch.cuda.is_current_stream_capturing():
+        return
+    need = ctx.check_status()
+    if need > 0:
+        cap = 1
+        while cap < need + need // 4:
+            cap <<= 1
+        ctx.reserve(0, cap)
+        ctx.check(call(), what)
+        need = ctx.check_status()
+        if need > 0:
+            raise DressiError(f"{what}: tile bins still overflow ({need} triangles per tile needed)")
+
+
 def scratch_bytes(B, V, T, H, W, K, r, Va=0, C_=0, tex_cells=0, tex_slices=0):
     return int(_lib.dressi_scratch_bytes(B, V, T, H, W, K, float(r), Va, C_, tex_cells, tex_slices))
 
@@ -238,9 +259,9 @@ def dressi_rasterize(pos_clip, tris, H, W, K=1, r=0.0, cull=0):
     bary = torch.empty((B, K, H, W, 2), dtype=torch.float32, device=dev)
     dist = torch.empty((B, K, H, W), dtype=torch.float32, device=dev) if r > 0 else None
     ctx = context(dev.index)
-    ctx.check(_lib.dressi_rasterize(ctx.handle, _ptr(pos_clip), _ptr(tris), B, V, T, H, W, K,
-                                    float(r), int(cull), _ptr(tri_id), _ptr(bary), _ptr(dist),
-                                    _stream()), "dressi_rasterize")
+    _checked_raster(ctx, lambda: _lib.dressi_rasterize(ctx.handle, _ptr(pos_clip), _ptr(tris), B, V, T, H, W, K,
+                                                       float(r), int(cull), _ptr(tri_id), _ptr(bary),
+                                                       _ptr(dist), _stream()), "dressi_rasterize")
     return tri_id, bary, dist
 
 
@@ -571,9 +592,10 @@ def dressi_rasterize_batched(pos_clip, tris, tri_view, views, H, W, K=1, cull=0)
     tid = torch.empty((1, K, H, W), dtype=torch.int32, device=dev)
     bary = torch.empty((1, K, H, W, 2), dtype=torch.float32, device=dev)
     ctx = context(dev.index)
-    ctx.check(_lib.dressi_rasterize_batched(ctx.handle, _ptr(pos_clip), _ptr(tris), _ptr(tri_view), _ptr(views),
-                                            n, V, T, H, W, K, cull, _ptr(tid), _ptr(bary), _stream()),
-              "dressi_rasterize_batched")
+    _checked_raster(ctx, lambda: _lib.dressi_rasterize_batched(ctx.handle, _ptr(pos_clip), _ptr(tris),
+                                                               _ptr(tri_view), _ptr(views), n, V, T, H, W, K,
+                                                               cull, _ptr(tid), _ptr(bary), _stream()),
+                    "dressi_rasterize_batched")
     return tid, bary
 
 

@@ -49,6 +49,7 @@ extern "C" int dressi_destroy(dressi_ctx *ctx) {
     if (ctx->scratch) (void)hipFree(ctx->scratch);
     if (ctx->status) (void)hipFree(ctx->status);
     if (ctx->counters) (void)hipFree(ctx->counters);
+    for (void *p : ctx->retired) (void)hipFree(p);
     delete ctx;
     return DRESSI_OK;
 }
@@ -63,15 +64,14 @@ static int grow(dressi_ctx *ctx, size_t bytes) {
     hipError_t e = hipSetDevice(ctx->device);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) return dressi_hip_check(ctx, e, "synchronize before scratch growth");
-    if (ctx->scratch) (void)hipFree(ctx->scratch);
-    ctx->scratch = nullptr;
-    ctx->scratch_bytes = 0;
-    e = hipMalloc(&ctx->scratch, nb);
-    if (e != hipSuccess) {
-        ctx->scratch = nullptr;
+    void *p = nullptr;
+    e = hipMalloc(&p, nb);
+    if (e != hipSuccess)
         return dressi_fail(ctx, DRESSI_ENOMEM, "scratch allocation of " + std::to_string(nb) +
                                                    " bytes failed: " + hipGetErrorString(e));
-    }
+    // the old arena is retired, not freed: graphs captured earlier use it
+    if (ctx->scratch) ctx->retired.push_back(ctx->scratch);
+    ctx->scratch = p;
     ctx->scratch_bytes = nb;
     return DRESSI_OK;
 }
@@ -99,17 +99,17 @@ int dressi_counters(dressi_ctx *ctx, size_t n, hipStream_t stream) {
     size_t nn = n + n / 4 + 4096;
     e = hipDeviceSynchronize();
     if (e != hipSuccess) return dressi_hip_check(ctx, e, "synchronize before counter growth");
-    if (ctx->counters) (void)hipFree(ctx->counters);
-    ctx->counters = nullptr;
-    ctx->counters_n = 0;
-    e = hipMalloc(&ctx->counters, nn * sizeof(int32_t));
-    if (e == hipSuccess) e = hipMemset(ctx->counters, 0, nn * sizeof(int32_t));
+    int32_t *p = nullptr;
+    e = hipMalloc(&p, nn * sizeof(int32_t));
+    if (e == hipSuccess) e = hipMemset(p, 0, nn * sizeof(int32_t));
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
-        if (ctx->counters) (void)hipFree(ctx->counters);
-        ctx->counters = nullptr;
+        if (p) (void)hipFree(p);
         return dressi_fail(ctx, DRESSI_ENOMEM, std::string("counter allocation failed: ") + hipGetErrorString(e));
     }
+    // retired like the arena (the kernels keep a retired array at zero)
+    if (ctx->counters) ctx->retired.push_back(ctx->counters);
+    ctx->counters = p;
     ctx->counters_n = nn;
     return DRESSI_OK;
 }

@@ -6,6 +6,7 @@
 
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "../../include/dressi.h"
 
@@ -24,6 +25,10 @@ struct dressi_ctx {
     int64_t *status = nullptr;  // device: [0] overflow flag, [1] bin capacity needed
     int32_t *counters = nullptr;  // device counters kept at zero between calls
     size_t counters_n = 0;
+    // Arenas and counter arrays replaced by larger ones.  A graph captured
+    // before the growth still holds their addresses, so they stay allocated
+    // (and the counters zero) until dressi_destroy.
+    std::vector<void *> retired;
     std::string err;
 };
 

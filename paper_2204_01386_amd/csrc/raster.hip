@@ -1342,6 +1342,10 @@ __global__ void k_rast_bwd_vertex(const float4 *__restrict__ pos_clip, Viewports
             const int c = adj.corners[j];
             const int t = c / 3, i = c - 3 * t;
             const int64_t key = (int64_t)b * T + t;
+            // a triangle without fragments adds nothing; it may be one that
+            // setup dropped for this vertex's w <= 0 or non-finite position,
+            // whose clip map below would not be finite
+            if (tt.offsets[key] == tt.offsets[key + 1]) continue;
             double a0 = 0.0, a1 = 0.0, a2 = 0.0;
             for (int e = tt.offsets[key]; e < tt.offsets[key + 1]; e++) {
                 const int2 ent = tt.entries[e];

@@ -380,6 +380,17 @@ class Step(_TwoStreams):
         self.loss_and_grad()
         self.backward()
 
+    def check_overflow(self):
+        """Raises if a rasterization since the last check (eager or a graph
+        replay) overflowed the tile bins, which leaves its outputs invalid.
+        The bins are calibrated on the scene at construction; a scene whose
+        geometry moves (an optimisation) checks after its steps.  Host
+        synchronisation; not for use while capturing."""
+        need = self.ctx.check_status()
+        if need > 0:
+            raise Bd.DressiError(f"tile bins overflowed ({need} triangles per tile needed): "
+                                 "the outputs since the last check are invalid; recalibrate")
+
     def rgba(self):
         """Rendered image [B,H,W,4] (colour, silhouette) as a new tensor."""
         return torch.cat([self.color, self.sil[..., None]], -1).contiguous()
@@ -729,6 +740,8 @@ class BatchStep(_TwoStreams):
         self.forward()
         self.loss_and_grad()
         self.backward()
+
+    check_overflow = Step.check_overflow
 
     def rgba(self):
         return torch.cat([self.color, self.sil[..., None]], -1).contiguous()
