@@ -153,6 +153,24 @@ int dressi_rasterize(dressi_ctx *ctx, const float *pos_clip, const int32_t *tris
                      int B, int V, int T, int H, int W, int K, float r, int cull,
                      int32_t *tri_id, float *bary, float *dist, void *stream);
 
+/* Edge-band form of dressi_rasterize for a HardSoftRas blend (§3.4.3): with
+ * the blend's edge mask E (dressi_softras with the same delta and mode), the
+ * image outside E is S^H C_1 and the silhouette S^H, so there only the front
+ * hard fragment reaches the image or any gradient.  The banded outputs equal
+ * dressi_rasterize's on every pixel of E; outside E, layer 0 is kept when it
+ * is hard (else empty) and layers 1..K-1 are empty.  E is built here from
+ * the front hard fragments (S^H does not depend on the soft layers), and the
+ * soft candidates are searched only in tiles that meet E.  blend_mode:
+ * DRESSI_BLEND_HSR (E = boundary of S^H dilated by ceil(delta W) - 1
+ * pixels), _AA (the boundary itself), _HARD (E empty), _SOFTRAS (E is every
+ * pixel: the full form).  Needs r > 0 and dist.  The blend's image, its
+ * silhouette and the gradients of positions and vertex attributes are those
+ * of the full form; texture gradients differ where the full form's pixels
+ * outside E (whose gradient is zero) win inverse-UV cells. */
+int dressi_rasterize_banded(dressi_ctx *ctx, const float *pos_clip, const int32_t *tris, int B, int V,
+                            int T, int H, int W, int K, float r, int cull, float delta, int blend_mode,
+                            int32_t *tri_id, float *bary, float *dist, void *stream);
+
 /* Backward of dressi_rasterize with frozen visibility: the gradients of bary
  * and dist carried to the clip-space vertices (Rasterize and PeelDepth have no
  * backward of their own; snapping is treated as the identity).  grad_bary

@@ -502,3 +502,24 @@ def texture_f32(tex, coord, tri_id=None, kind=TEX_2D, wrap_u=WRAP_REPEAT, wrap_v
     tid = _i32(tri_id) if tri_id is not None else None
     _check(f(_p(t), C.byref(d), _p(c), _p(tid), N, _p(out)), "texture_f32")
     return out
+
+
+def band_layers(tri_id, hard, bary, dist, delta, mode=BLEND_HSR):
+    """The edge-band form of rasterized layers for a blend of this delta and
+    mode (§3.4.3: outside the blend's edge mask E the image is S^H C_1 and
+    the silhouette S^H, so only the front hard fragment reaches them there).
+    Inside E the layers are kept; outside E layer 0 is kept when it is hard
+    and every other entry is emptied (tri_id -1, hard 0, bary 0, dist 0).
+    E is the blend's own mask of these layers (edge_mask)."""
+    tid = np.array(tri_id, np.int32)
+    hd = np.array(hard, np.uint8)
+    ba = np.array(bary, np.float64)
+    di = np.array(dist, np.float64)
+    E = edge_mask(tid, di, delta, mode).astype(bool)[:, None]          # [B,1,H,W]
+    keep = np.broadcast_to(E, tid.shape).copy()
+    keep[:, 0] |= hd[:, 0].astype(bool)
+    tid[~keep] = -1
+    hd[~keep] = 0
+    ba[~keep] = 0.0
+    di[~keep] = 0.0
+    return tid, hd, ba, di

@@ -33,6 +33,14 @@ def _params(scene, target):
     return pos, color, tex
 
 
+def banded(scene):
+    """Whether the scene's layers take the edge-band form (the default for
+    the HardSoftRas and anti-aliasing blends with a soft reach; a scene sets
+    extra["band"] = False for the full form)."""
+    blend = scene.extra.get("blend", "hsr" if scene.r > 0 else "hard")
+    return scene.r > 0 and blend in ("hsr", "aa") and bool(scene.extra.get("band", True))
+
+
 def forward(scene, views=None, target=False, window=None):
     """Forward of the scene's views.  window = (x0, y0, w, h): only the
     pixels of that rectangle of each H x W image (every triangle considered;
@@ -60,6 +68,14 @@ def forward(scene, views=None, target=False, window=None):
         tid, hard, bary, dist = O.rasterize(pc, tris, H, W, K=K, r=r)
     else:
         tid, hard, bary, dist = O.rasterize_window(pc, tris, H, W, window, K=K, r=r)
+    # the blend setting of §3.4.3: HardSoftRas with delta = r by default; a
+    # scene may choose the anti-aliasing or SoftRas-like settings instead
+    blend = {"hsr": O.BLEND_HSR, "aa": O.BLEND_AA, "softras": O.BLEND_SOFTRAS,
+             "hard": O.BLEND_HARD}[scene.extra.get("blend", "hsr" if r > 0 else "hard")]
+    # the dilation radius ceil(delta * width) - 1 is set by the image width
+    delta = r if window is None else r * W / window[2]
+    if banded(scene):
+        tid, hard, bary, dist = O.band_layers(tid, hard, bary, dist, delta, blend)
     gb = O.interpolate(vattr, tris, tid, bary)
     # the shading's inputs: the per-vertex rows rounded once to float, then
     # interpolated in float (decision values, see the module docstring)
@@ -89,12 +105,6 @@ def forward(scene, views=None, target=False, window=None):
         st.update(shade_n=shade_n, dir=d, env_s=env_s)
     col = O.shade(mode, shade_n, p if mode != O.SHADE_LAMBERT else None, albedo, env_s, eye, tid)
     sigma = r / 7.0 if r > 0 else 1.0
-    # the blend setting of §3.4.3: HardSoftRas with delta = r by default; a
-    # scene may choose the anti-aliasing or SoftRas-like settings instead
-    blend = {"hsr": O.BLEND_HSR, "aa": O.BLEND_AA, "softras": O.BLEND_SOFTRAS,
-             "hard": O.BLEND_HARD}[scene.extra.get("blend", "hsr" if r > 0 else "hard")]
-    # the dilation radius ceil(delta * width) - 1 is set by the image width
-    delta = r if window is None else r * W / window[2]
     oc, os_, E = O.softras(col, st["dist"], tid, sigma, delta, blend)
     st.update(layer_color=col, albedo=albedo, color=oc, sil=os_, E=E, sigma=sigma)
     st["rgba"] = np.concatenate([oc, os_[..., None]], -1)

@@ -82,6 +82,7 @@ _SIG = {
     "dressi_reserve": [_vp, _sz, _i64],
     "dressi_check_status": [_vp, C.POINTER(C.c_int64), _vp],
     "dressi_rasterize": [_vp, _vp, _vp, _i, _i, _i, _i, _i, _i, _f, _i, _vp, _vp, _vp, _vp],
+    "dressi_rasterize_banded": [_vp, _vp, _vp, _i, _i, _i, _i, _i, _i, _f, _i, _f, _i, _vp, _vp, _vp, _vp],
     "dressi_rasterize_bwd": [_vp, _vp, _vp, _i, _i, _i, _i, _i, _i, _f, _i, _vp, _vp, _vp, _vp, _vp,
                              _vp, _vp],
     "dressi_interpolate": [_vp, _vp, _i, _i, _i, _vp, _i, _vp, _vp, _i, _i, _i, _i, _vp, _vp],
@@ -262,6 +263,26 @@ def dressi_rasterize(pos_clip, tris, H, W, K=1, r=0.0, cull=0):
     _checked_raster(ctx, lambda: _lib.dressi_rasterize(ctx.handle, _ptr(pos_clip), _ptr(tris), B, V, T, H, W, K,
                                                        float(r), int(cull), _ptr(tri_id), _ptr(bary),
                                                        _ptr(dist), _stream()), "dressi_rasterize")
+    return tri_id, bary, dist
+
+
+def dressi_rasterize_banded(pos_clip, tris, H, W, K, r, delta, mode=BLEND_HSR, cull=0):
+    """Edge-band form of dressi_rasterize for a blend of the given delta and
+    mode: the full layers inside the blend's edge mask, the front hard
+    fragment alone outside it."""
+    _need(pos_clip, torch.float32, "pos_clip")
+    _need(tris, torch.int32, "tris")
+    B, V, _ = pos_clip.shape
+    T = tris.shape[0]
+    dev = pos_clip.device
+    tri_id = torch.empty((B, K, H, W), dtype=torch.int32, device=dev)
+    bary = torch.empty((B, K, H, W, 2), dtype=torch.float32, device=dev)
+    dist = torch.empty((B, K, H, W), dtype=torch.float32, device=dev)
+    ctx = context(dev.index)
+    _checked_raster(ctx, lambda: _lib.dressi_rasterize_banded(ctx.handle, _ptr(pos_clip), _ptr(tris), B, V, T, H,
+                                                              W, K, float(r), int(cull), float(delta), int(mode),
+                                                              _ptr(tri_id), _ptr(bary), _ptr(dist), _stream()),
+                    "dressi_rasterize_banded")
     return tri_id, bary, dist
 
 

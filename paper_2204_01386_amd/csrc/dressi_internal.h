@@ -41,6 +41,12 @@ int dressi_hip_check(dressi_ctx *ctx, hipError_t e, const char *what);
 // fails with DRESSI_ENOMEM while `stream` is capturing.
 int dressi_scratch(dressi_ctx *ctx, size_t bytes, hipStream_t stream);
 int dressi_launch_check(dressi_ctx *ctx, const char *what);
+// The blend's edge mask (softras.hip): S^H from layer 0 of tri_id (hard where
+// the sign bit of dist is clear, all present fragments when dist is NULL),
+// its 4-neighbour boundary `bnd`, the row pass `rows` and the mask `edge`
+// (L-infinity dilation of radius rho >= 0), one byte per pixel [B,H,W].
+void dressi_edge_mask(const int32_t *tri_id, const float *dist, int B, int K, int H, int W, int rho,
+                      uint8_t *bnd, uint8_t *rows, uint8_t *edge, hipStream_t st);
 // Looks up, once per device, the device address of the fixed scratch of
 // dressi_softras_noalloc (softras.hip); `device` must be current.
 int dressi_softras_noalloc_setup(int device);

@@ -524,12 +524,25 @@ __device__ __forceinline__ int wave_max_i(int v) {
     return v;
 }
 
-template <int K, bool SOFT, bool HYB = false>
+// Edge-band soft rasterization (BAND != 0).  Outside the blend's edge mask E
+// the image is S^H C_1 and the silhouette S^H (§3.4.3), so only the front
+// hard fragment of a pixel reaches the image or a gradient there.  The
+// banded contract keeps, outside E, layer 0 if it is hard and nothing else,
+// and the full K layers inside E.  BAND = 1 is its first pass: every tile,
+// covering triangles only, hard fragments only, writing layer 0 (the front
+// hard fragment, with its distance) and empty layers 1..K-1; E is then built
+// from that layer 0 (its S^H equals the full form's); BAND = 2 is the second
+// pass: tiles with a pixel in E rasterize fully (the full form's walks) and
+// write the K layers of their E pixels; other tiles exit at once.
+template <int K, bool SOFT, bool HYB = false, int BAND = 0>
 __global__ void __launch_bounds__(DRESSI_TILE_PIX) __attribute__((amdgpu_waves_per_eu(SOFT ? 7 : 5)))
     k_raster_list(const TriSetup *__restrict__ setup, int32_t *__restrict__ counts,
                   const int32_t *__restrict__ bins, int cap, int T, int H, int W, int ntx, int nt,
                   float r, int32_t *__restrict__ tri_id, float2 *__restrict__ bary,
-                  float *__restrict__ dist, int hyb_w) {
+                  float *__restrict__ dist, int hyb_w, const uint8_t *__restrict__ band, int keep_counts) {
+    static_assert(BAND == 0 || SOFT, "banding is for soft rasterization");
+    constexpr bool SM = SOFT && BAND != 1;   // soft fragments merged
+    constexpr int KL = BAND == 1 ? 1 : K;    // layers kept in registers
     // staged triangles (structure of arrays)
     __shared__ int2 sfi[RL_BATCH];      // meta | 32-bit-exact flag << 16, triangle id
     __shared__ int2 sbox[RL_BATCH];     // soft box
@@ -566,11 +579,20 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX) __attribute__((amdgpu_waves_p
     const int py0 = DRESSI_SUBPIX * (ty * DRESSI_TILE) + DRESSI_SUBPIX / 2;
     int nbin = counts[bt];
     if (nbin > cap) nbin = cap;
+    bool inE = true;   // this lane's pixel is in the edge mask (the second banded pass)
+    if (BAND == 2) {
+        inE = x < W && y < H && band[((int64_t)b * H + y) * W + x] != 0;
+        if (!__syncthreads_or(inE)) {
+            if (p == 0) counts[bt] = 0;
+            return;
+        }
+    }
+    const bool waveE = BAND != 2 || __ballot(inE) != 0ull;
 
-    float key[K];
-    int id[K];
+    float key[KL];
+    int id[KL];
 #pragma unroll
-    for (int k = 0; k < K; k++) {
+    for (int k = 0; k < KL; k++) {
         key[k] = 2.0f;   // empty: above every fragment key
         id[k] = -1;
     }
@@ -581,7 +603,7 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX) __attribute__((amdgpu_waves_p
         if (p < 4) scost[p >> 1][p & 1] = 0;
     }
 
-    for (int walk = 0; walk < (SOFT ? 3 : 1); walk++) {   // hard only: covering triangles
+    for (int walk = 0; walk < (SM ? 3 : 1); walk++) {   // hard only: covering triangles
         for (int c0 = 0; c0 < nbin; c0 += RL_BATCH) {
             const int n = min(RL_BATCH, nbin - c0);
             const int par = (c0 / RL_BATCH) & 1;
@@ -591,7 +613,22 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX) __attribute__((amdgpu_waves_p
                 // the other parity's costs were read before this barrier
                 if (HYB && p < 2) scost[par ^ 1][p] = 0;
                 int tp_pix = 0, pp_steps = 0;
-                if (p < n) {
+                bool stage = p < n;
+                if (BAND == 1 && stage) {
+                    // the first banded pass takes covering triangles only: one
+                    // whose vertex box misses this tile is marked far away
+                    // (never wanted by the covering walk) without loading
+                    // the rest of its record
+                    const int2 hb = *reinterpret_cast<const int2 *>(&sv[bin[c0 + p]].hbox0);
+                    const int ty0 = ty * DRESSI_TILE, ty1 = ty0 + DRESSI_TILE - 1;
+                    if (hi16(hb.x) < wx0 || lo16(hb.x) > wx1 || hi16(hb.y) < ty0 || lo16(hb.y) > ty1) {
+                        shb[p] = make_int2((int)0x80008000u, (int)0x80008000u);
+                        sbox[p] = make_int2(0, 0);
+                        szlb[p] = 0;
+                        stage = false;
+                    }
+                }
+                if (stage) {
                     const int t = bin[c0 + p];
                     const TriSetup s = sv[t];
                     // 32-bit integer path: every pixel-to-vertex difference over the
@@ -653,8 +690,8 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX) __attribute__((amdgpu_waves_p
                     const int gy = max(max(lo16(hb.y) - wy1, wy0 - hi16(hb.y)), 0);
                     const int g = max(gx, gy);
                     if (walk == 0) want = hit && g == 0 && szlb[e] <= wmax_bits;
-                    else if (walk == 1) want = hit && g > 0 && g <= RL_NEAR && g <= gap_max;
-                    else want = hit && g > RL_NEAR && g <= gap_max;
+                    else if (walk == 1) want = waveE && hit && g > 0 && g <= RL_NEAR && g <= gap_max;
+                    else want = waveE && hit && g > RL_NEAR && g <= gap_max;
                 }
                 unsigned long long todo = __ballot(want);
                 while (todo) {
@@ -673,6 +710,7 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX) __attribute__((amdgpu_waves_p
                     s.Af = z4.w;
                     s.meta = fl & 0xffff;
                     const float el[3] = {e4.x, e4.y, e4.z};
+                    if (BAND == 2 && !inE) continue;
                     if (fl >> 16) {
                         // exact in 32-bit integers (see the staging test)
                         int ex[3], ey[3], len2[3];
@@ -691,21 +729,21 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX) __attribute__((amdgpu_waves_p
                             E[i] = __mul24(ex[i], qy[a]) - __mul24(ey[i], qx[a]);
                         }
                         if (walk == 0)
-                            rl_merge<K, true, int, SOFT>(s, E, el, t, px, py, dscale, r, reach, key, id, qx, qy, ex,
-                                                         ey, len2);
+                            rl_merge<KL, true, int, SM>(s, E, el, t, px, py, dscale, r, reach, key, id, qx, qy, ex,
+                                                        ey, len2);
                         else
-                            rl_merge<K, false, int, SOFT>(s, E, el, t, px, py, dscale, r, reach, key, id, qx, qy, ex,
-                                                          ey, len2);
+                            rl_merge<KL, false, int, SM>(s, E, el, t, px, py, dscale, r, reach, key, id, qx, qy, ex,
+                                                         ey, len2);
                     } else {
                         double E[3];
 #pragma unroll
                         for (int i = 0; i < 3; i++) E[i] = dr_edge(s.X, s.Y, i, px, py);
-                        if (walk == 0) rl_merge<K, true, double, SOFT>(s, E, el, t, px, py, dscale, r, reach, key, id);
-                        else rl_merge<K, false, double, SOFT>(s, E, el, t, px, py, dscale, r, reach, key, id);
+                        if (walk == 0) rl_merge<KL, true, double, SM>(s, E, el, t, px, py, dscale, r, reach, key, id);
+                        else rl_merge<KL, false, double, SM>(s, E, el, t, px, py, dscale, r, reach, key, id);
                     }
                 }
                 // keys only decrease: refresh the strip's bounds
-                const float wm = wave_max(key[K - 1]);
+                const float wm = wave_max(BAND == 2 && !inE ? 0.0f : key[KL - 1]);
                 wmax_bits = __float_as_int(wm);
                 // a soft candidate needs dn <= 2 (wmax - 0.5) + one key rounding;
                 // a pixel gap g (L-infinity, whole pixels) gives dn > (g - 1) / W
@@ -726,8 +764,20 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX) __attribute__((amdgpu_waves_p
             }
         }
     }
-    if (p == 0) counts[bt] = 0;   // every lane has read it before the first barrier
-    resolve_store<K, SOFT>(sv, key, id, b, x, y, px, py, H, W, dscale, tri_id, bary, dist);
+    if (p == 0 && !keep_counts) counts[bt] = 0;   // every lane has read it before the first barrier
+    if (BAND == 2 && !inE) return;
+    if constexpr (KL == K) {
+        resolve_store<K, SOFT>(sv, key, id, b, x, y, px, py, H, W, dscale, tri_id, bary, dist);
+    } else {
+        float kk[K];
+        int ii[K];
+#pragma unroll
+        for (int k = 0; k < K; k++) {
+            kk[k] = k < KL ? key[k] : 2.0f;
+            ii[k] = k < KL ? id[k] : -1;
+        }
+        resolve_store<K, SOFT>(sv, kk, ii, b, x, y, px, py, H, W, dscale, tri_id, bary, dist);
+    }
 }
 
 // Hard rasterization has two strategies with identical results (the layer
@@ -740,13 +790,13 @@ static void launch_raster_k(bool soft, int hard_pix, int hyb_w, dim3 g, hipStrea
                             float r, int32_t *tid, float2 *bary, float *dist) {
     if (soft)
         DR_LAUNCH("k_raster_list", (k_raster_list<K, true>), g, DRESSI_TILE_PIX, 0, st, setup, counts, bins, cap,
-                  T, H, W, ntx, nt, r, tid, bary, dist, 0);
+                  T, H, W, ntx, nt, r, tid, bary, dist, 0, nullptr, 0);
     else if (hard_pix == 2 && K == 1)
         DR_LAUNCH("k_raster_list", (k_raster_list<1, false, true>), g, DRESSI_TILE_PIX, 0, st, setup, counts,
-                  bins, cap, T, H, W, ntx, nt, r, tid, bary, dist, hyb_w);
+                  bins, cap, T, H, W, ntx, nt, r, tid, bary, dist, hyb_w, nullptr, 0);
     else if (hard_pix)
         DR_LAUNCH("k_raster_list", (k_raster_list<K, false>), g, DRESSI_TILE_PIX, 0, st, setup, counts, bins,
-                  cap, T, H, W, ntx, nt, r, tid, bary, dist, 0);
+                  cap, T, H, W, ntx, nt, r, tid, bary, dist, 0, nullptr, 0);
     else
         DR_LAUNCH("k_raster", (k_raster<K, false>), g, DRESSI_TILE_PIX, 0, st, setup, counts, bins, cap, T, H,
                   W, ntx, nt, r, tid, bary, dist);
@@ -791,9 +841,11 @@ static int check_raster_args(dressi_ctx *ctx, const void *pos, const void *tris,
     return DRESSI_OK;
 }
 
+// band: -2 = the full form; otherwise the edge-band form of a blend whose
+// edge mask is empty (-1) or the boundary of S^H dilated by band >= 0 pixels.
 static int rasterize_impl(dressi_ctx *ctx, const float *pos_clip, const int32_t *tris, Viewports vp, int B,
                           int V, int T, int H, int W, int K, float r, int cull, int32_t *tri_id, float *bary,
-                          float *dist, void *stream) {
+                          float *dist, void *stream, int band = -2) {
     int rc = check_raster_args(ctx, pos_clip, tris, B, V, T, H, W, K, r);
     if (rc) return rc;
     if (!tri_id || !bary) return dressi_fail(ctx, DRESSI_EINVAL, "rasterize: null tri_id or bary");
@@ -804,9 +856,11 @@ static int rasterize_impl(dressi_ctx *ctx, const float *pos_clip, const int32_t 
     int ntx = tiles_x(W), nty = tiles_y(H), nt = ntx * nty;
     int margin = soft_margin(r, W);
     int cap = tile_capacity(ctx, B, T, nt, margin);
+    const bool banded = soft && band >= -1;
     Carver c;
     size_t o[2];
     raster_scratch(B, T, nt, cap, c, o);
+    const size_t o_band = banded ? c.take(3 * (size_t)B * H * W) : 0;   // boundary, rows, edge mask
     rc = dressi_scratch(ctx, c.off, st);
     if (rc) return rc;
     rc = dressi_counters(ctx, (size_t)B * nt, st);
@@ -822,6 +876,35 @@ static int rasterize_impl(dressi_ctx *ctx, const float *pos_clip, const int32_t 
                   nt, cap, setup, counts, bins, reinterpret_cast<unsigned long long *>(ctx->status));
     dim3 g((unsigned)(B * nt));
     float2 *b2 = reinterpret_cast<float2 *>(bary);
+    if (banded) {
+        // first pass: the front hard fragment of every pixel (the bins are
+        // read again by the second pass, so their counts are kept)
+        uint8_t *bnd = at<uint8_t>(S, o_band);
+        uint8_t *rows = bnd + (size_t)B * H * W, *edge = rows + (size_t)B * H * W;
+        const int keep = band >= 0 ? 1 : 0;
+        switch (K) {
+#define DR_BAND1(KK)                                                                                       \
+    case KK:                                                                                               \
+        DR_LAUNCH("k_raster_list_band1", (k_raster_list<KK, true, false, 1>), g, DRESSI_TILE_PIX, 0, st, setup, \
+                  counts, bins, cap, T, H, W, ntx, nt, r, tri_id, b2, dist, 0, nullptr, keep);            \
+        break;
+            DR_BAND1(1) DR_BAND1(2) DR_BAND1(3) DR_BAND1(4) DR_BAND1(5)
+#undef DR_BAND1
+        }
+        if (band >= 0) {
+            dressi_edge_mask(tri_id, dist, B, K, H, W, band, bnd, rows, edge, st);
+            switch (K) {
+#define DR_BAND2(KK)                                                                                       \
+    case KK:                                                                                               \
+        DR_LAUNCH("k_raster_list", (k_raster_list<KK, true, false, 2>), g, DRESSI_TILE_PIX, 0, st, setup,    \
+                  counts, bins, cap, T, H, W, ntx, nt, r, tri_id, b2, dist, 0, edge, 0);                  \
+        break;
+                DR_BAND2(1) DR_BAND2(2) DR_BAND2(3) DR_BAND2(4) DR_BAND2(5)
+#undef DR_BAND2
+            }
+        }
+        return dressi_launch_check(ctx, "rasterize_banded");
+    }
     const int hp = ctx->hard_raster, hw = ctx->hybrid_weight;
     switch (K) {
     case 1: launch_raster_k<1>(soft, hp, hw, g, st, setup, counts, bins, cap, T, H, W, ntx, nt, r, tri_id, b2, dist); break;
@@ -838,6 +921,23 @@ extern "C" int dressi_rasterize(dressi_ctx *ctx, const float *pos_clip, const in
                                 int32_t *tri_id, float *bary, float *dist, void *stream) {
     return rasterize_impl(ctx, pos_clip, tris, Viewports{nullptr, nullptr}, B, V, T, H, W, K, r, cull, tri_id,
                           bary, dist, stream);
+}
+
+extern "C" int dressi_rasterize_banded(dressi_ctx *ctx, const float *pos_clip, const int32_t *tris, int B,
+                                       int V, int T, int H, int W, int K, float r, int cull, float delta,
+                                       int blend_mode, int32_t *tri_id, float *bary, float *dist, void *stream) {
+    if (!ctx) return DRESSI_EINVAL;
+    if (!(r > 0.0f)) return dressi_fail(ctx, DRESSI_EINVAL, "rasterize_banded: needs a soft reach r > 0");
+    int band;
+    switch (blend_mode) {
+    case DRESSI_BLEND_HSR: band = std::max((int)ceilf(delta * (float)W) - 1, -1); break;
+    case DRESSI_BLEND_AA: band = 0; break;
+    case DRESSI_BLEND_SOFTRAS: band = -2; break;   // the edge mask is everything: the full form
+    case DRESSI_BLEND_HARD: band = -1; break;
+    default: return dressi_fail(ctx, DRESSI_EINVAL, "rasterize_banded: bad blend mode");
+    }
+    return rasterize_impl(ctx, pos_clip, tris, Viewports{nullptr, nullptr}, B, V, T, H, W, K, r, cull, tri_id,
+                          bary, dist, stream, band);
 }
 
 static int check_views(dressi_ctx *ctx, const int32_t *tri_view, const void *views, int n, int T) {

@@ -47,6 +47,33 @@ __global__ void k_dilate_rows(const uint8_t *__restrict__ bnd, int B, int H, int
     rows[gid] = v;
 }
 
+// column pass of the dilation, written out as the edge mask itself (the blend
+// fuses this pass; the banded rasterizer needs the mask before any blend)
+__global__ void k_dilate_cols(const uint8_t *__restrict__ rows, int B, int H, int W, int rho,
+                              uint8_t *__restrict__ edge) {
+    int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t N = (int64_t)H * W;
+    if (gid >= (int64_t)B * N) return;
+    int b = (int)(gid / N);
+    int p = (int)(gid - (int64_t)b * N);
+    int y = p / W, x = p - y * W;
+    int a = max(y - rho, 0), e = min(y + rho, H - 1);
+    const uint8_t *col = rows + (int64_t)b * N + x;
+    uint8_t v = 0;
+    for (int q = a; q <= e && !v; q++) v = col[(int64_t)q * W];
+    edge[gid] = v;
+}
+
+void dressi_edge_mask(const int32_t *tri_id, const float *dist, int B, int K, int H, int W, int rho,
+                      uint8_t *bnd, uint8_t *rows, uint8_t *edge, hipStream_t st) {
+    const int64_t n = (int64_t)B * H * W;
+    if (n == 0) return;
+    const int g = (int)((n + 255) / 256);
+    DR_LAUNCH("k_boundary", (k_boundary), g, 256, 0, st, tri_id, dist, B, K, H, W, bnd);
+    DR_LAUNCH("k_dilate_rows", (k_dilate_rows), g, 256, 0, st, bnd, B, H, W, rho, rows);
+    DR_LAUNCH("k_dilate_cols", (k_dilate_cols), g, 256, 0, st, rows, B, H, W, rho, edge);
+}
+
 // sigmoid(x) and 1 - sigmoid(x) = sigmoid(-x), each to full relative
 // precision: the complement is never formed by subtracting from 1, which
 // would lose it where the sigmoid is near 1 (its derivative w (1 - w) and

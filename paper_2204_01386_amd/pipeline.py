@@ -152,6 +152,11 @@ class Step(_TwoStreams):
             raise ValueError(f"blend {blend!r} needs a soft reach r > 0")
         self.sigma = self.r / 7.0 if self.r > 0 else 1.0
         self.delta = self.r
+        # edge-band rasterization (the default for the HardSoftRas and
+        # anti-aliasing blends): the soft layers only where the blend's edge
+        # mask reaches; scene.extra["band"] = False keeps the full form
+        self.band = (self.r > 0 and self.blend in (Bd.BLEND_HSR, Bd.BLEND_AA)
+                     and bool(scene.extra.get("band", True)))
         # per-vertex attributes: normal, position, extra (colour or tangent)
         self.extra = None
         if self.mode == Bd.SHADE_LAMBERT:
@@ -239,9 +244,15 @@ class Step(_TwoStreams):
         self.ctx.tune(Bd.TUNE_HYBRID_WEIGHT, self.hybrid_weight)
         self._chk(_lib.dressi_transform(h, _p(self.pos), _p(self.mvp), self.B, self.V, _p(self.pos_clip), st),
                   "transform")
-        self._chk(_lib.dressi_rasterize(h, _p(self.pos_clip), _p(self.tris), self.B, self.V, self.T, self.H,
-                                        self.W, self.K, self.r, 0, _p(self.tri_id), _p(self.bary),
-                                        _p(self.dist), st), "rasterize")
+        if self.band:
+            self._chk(_lib.dressi_rasterize_banded(h, _p(self.pos_clip), _p(self.tris), self.B, self.V, self.T,
+                                                   self.H, self.W, self.K, self.r, 0, self.delta, self.blend,
+                                                   _p(self.tri_id), _p(self.bary), _p(self.dist), st),
+                      "rasterize_banded")
+        else:
+            self._chk(_lib.dressi_rasterize(h, _p(self.pos_clip), _p(self.tris), self.B, self.V, self.T, self.H,
+                                            self.W, self.K, self.r, 0, _p(self.tri_id), _p(self.bary),
+                                            _p(self.dist), st), "rasterize")
 
     def _calibrate_bins(self):
         """Rasterizes once and grows the tile-bin capacity until no tile

@@ -522,6 +522,9 @@ def config5(seed: int = 0, n_views: int = 8, H: int = 2048, nu: int = 2048, nv: 
               tex=value_noise(tex_size, tex_size, 4, seed), target_pos=tp,
               target_tex=value_noise(tex_size, tex_size, 4, seed + 1))
     s.extra["wrap"] = (0, 0)   # repeat in u and v
+    # the full form of the layers: at this reach (20 px) the blend's edge band
+    # covers nearly the whole tube, so the edge-band form saves no soft work
+    s.extra["band"] = False
     return s
 
 

@@ -60,16 +60,29 @@ def _windows(tid0, H, W, seed):
     return [(min(max(x, 0), W - WIN), min(max(y, 0), H - WIN), WIN, WIN) for x, y in out]
 
 
+def _margin_region(x0, y0, w, h, H, W, m):
+    rx0, ry0 = max(0, x0 - m), max(0, y0 - m)
+    rx1, ry1 = min(W, x0 + w + m), min(H, y0 + h + m)
+    return (rx0, ry0, rx1 - rx0, ry1 - ry0), (slice(y0 - ry0, y0 - ry0 + h), slice(x0 - rx0, x0 - rx0 + w))
+
+
 def test_config5_raster_windows(cfg5, step5, clip5):
+    """The step's layers (edge-band form) in sampled windows: the oracle
+    rasterizes the window plus the margin its edge mask reads, reduces the
+    layers by that mask and crops."""
     H, W, K, r = cfg5.H, cfg5.W, cfg5.K, cfg5.r
+    assert step5.band
+    mg = math.ceil(r * W) - 1 + 2
     tid_all = host(step5.tri_id)
     bary_all = host(step5.bary)
     dist_all = host(step5.dist)
     assert (tid_all[:, 0] >= 0).mean() > 0.05, "the knot should cover part of every image"
     for v in range(tid_all.shape[0]):
         for (x0, y0, w, h) in _windows(tid_all[v, 0], H, W, seed=v):
-            tid_o, hard_o, bary_o, dist_o = oracle.rasterize_window(clip5[v:v + 1], cfg5.tris, H, W,
-                                                                    (x0, y0, w, h), K=K, r=r)
+            reg, sl = _margin_region(x0, y0, w, h, H, W, mg)
+            full = oracle.rasterize_window(clip5[v:v + 1], cfg5.tris, H, W, reg, K=K, r=r)
+            banded = oracle.band_layers(*full, r * W / reg[2], oracle.BLEND_HSR)
+            tid_o, hard_o, bary_o, dist_o = (a[:, :, sl[0], sl[1]] for a in banded)
             tid_g = tid_all[v:v + 1, :, y0:y0 + h, x0:x0 + w]
             assert np.array_equal(tid_g, tid_o), \
                 f"view {v} window {(x0, y0)}: tri_id differs at {np.argwhere(tid_g != tid_o)[:5].tolist()}"
@@ -98,10 +111,8 @@ def test_config5_image_windows(cfg5, step5, clip5):
     tid_all = host(step5.tri_id)
     for v in (0, 3, 6):
         for (x0, y0, w, h) in _windows(tid_all[v, 0], H, W, seed=100 + v)[:2]:
-            rx0, ry0 = max(0, x0 - m), max(0, y0 - m)
-            rx1, ry1 = min(W, x0 + w + m), min(H, y0 + h + m)
-            oc, osil, oE = _oracle_window_image(cfg5, clip5, v, (rx0, ry0, rx1 - rx0, ry1 - ry0))
-            sl = (slice(y0 - ry0, y0 - ry0 + h), slice(x0 - rx0, x0 - rx0 + w))
+            reg, sl = _margin_region(x0, y0, w, h, H, W, m)
+            oc, osil, oE = _oracle_window_image(cfg5, clip5, v, reg)
             assert np.array_equal(E[v, y0:y0 + h, x0:x0 + w], oE[0][sl]), f"view {v}: edge mask differs"
             assert_vals_close(color[v, y0:y0 + h, x0:x0 + w], oc[0][sl], what="colour")
             assert_vals_close(sil[v, y0:y0 + h, x0:x0 + w], osil[0][sl], what="silhouette")

@@ -182,6 +182,50 @@ def test_raster_config3_views_full_size(B):
     check_raster(B, pc, s.tris, 512, 512, 3, 0.01, seed=8)
 
 
+@pytest.mark.parametrize("mode,K,r,delta,views,HW", [
+    (0, 3, 0.04, 0.04, 3, (100, 75)),     # HardSoftRas: boundary dilated by ceil(delta W) - 1
+    (0, 2, 0.06, 0.02, 2, (90, 90)),
+    (0, 1, 0.05, 0.02, 1, (64, 80)),
+    (0, 3, 0.02, 0.001, 2, (96, 96)),     # ceil(delta W) - 1 = 0: the boundary itself
+    (1, 2, 0.05, 0.0, 2, (80, 64)),       # anti-aliasing: the boundary
+    (3, 3, 0.05, 0.0, 2, (72, 72)),       # hard blend: no edge mask, front hard fragments only
+    (2, 2, 0.05, 0.0, 1, (64, 64)),       # SoftRas-like: everything, the full form
+])
+def test_raster_banded(B, mode, K, r, delta, views, HW):
+    """The edge-band form: the oracle's full layers reduced by its own blend
+    edge mask (inside E every layer, outside it the front hard fragment
+    alone); tri_id bit-exact, values and the rasterization adjoint."""
+    H, W = HW
+    pc, tris = sphere_scene(subdiv=3, views=views, seed=6 + K)
+    full = oracle.rasterize(pc, tris, H, W, K=K, r=r)
+    tid_o, hard_o, bary_o, dist_o = oracle.band_layers(*full, delta, mode)
+    tid, bary, dist = B.dressi_rasterize_banded(dev(pc), dev(tris), H, W, K, r, delta, mode)
+    tid_g = host(tid)
+    assert np.array_equal(tid_g, tid_o), f"tri_id differs at {np.argwhere(tid_g != tid_o)[:5].tolist()}"
+    assert_vals_close(host(bary), bary_o, what="bary", scale_by_ref=True)
+    d = host(dist)
+    assert_vals_close(d, dist_o, what="dist")
+    m = tid_o >= 0
+    assert np.array_equal(np.signbit(d[m]), hard_o[m] == 0), "hard/soft sign differs"
+    if mode != 2:
+        assert (tid_o != full[0]).any(), "the band should empty some entries"
+    rng = np.random.default_rng(K)
+    gb = rng.standard_normal(bary_o.shape).astype(np.float32)
+    gd = rng.standard_normal(tid_o.shape).astype(np.float32)
+    gp = B.dressi_rasterize_bwd(dev(pc), dev(tris), tid, dev(gb), dev(gd), r)
+    gp_o = oracle.rasterize_bwd(pc, tris, tid_o, hard_o, gb.astype(np.float64), gd.astype(np.float64))
+    assert_grad_close(host(gp), gp_o, what="grad_pos_clip")
+
+
+def test_raster_banded_config3_full_size(B):
+    s = scenes.config3()
+    pc = to_clip(s.pos, s.mvp[:2])
+    full = oracle.rasterize(pc, s.tris, 512, 512, K=3, r=0.01)
+    tid_o = oracle.band_layers(*full, 0.01, oracle.BLEND_HSR)[0]
+    tid, _, _ = B.dressi_rasterize_banded(dev(pc), dev(s.tris), 512, 512, 3, 0.01, 0.01, B.BLEND_HSR)
+    assert np.array_equal(host(tid), tid_o)
+
+
 @pytest.mark.parametrize("hr,w", [(1, 40), (2, 1), (2, 40), (2, 1024)])
 def test_raster_hard_strategies(B, hr, w):
     """Every hard-rasterization strategy selects exactly the oracle's layers:

@@ -182,20 +182,48 @@ def test_step_config2_full(B):
 
 
 @pytest.mark.timeout(900)
-def test_step_config3_sixteen_views(B):
+@pytest.mark.parametrize("band", [True, False])
+def test_step_config3_sixteen_views(B, band):
     """The 16-view HardSoftRas step the benchmark times (one graph-capturable
     step over all views), every view and every gradient against the oracle:
     images 1e-5, gradients of positions, texture (albedo and normal map) and
-    environment map at rel 1e-4 in norm and element-wise."""
-    _compare_step(scenes.config3(), chunk=4)
+    environment map at rel 1e-4 in norm and element-wise; in the edge-band
+    form of the layers (the step's default) and in the full form."""
+    s = scenes.config3()
+    s.extra["band"] = band
+    _compare_step(s, chunk=4)
 
 
-@pytest.mark.parametrize("blend,K,r", [("aa", 1, 2 / 128), ("softras", 3, 0.02), ("hsr", 2, 0.01)])
-def test_step_blend_settings(B, blend, K, r):
+def test_step_band_keeps_image_and_position_gradient(B):
+    """The edge-band form changes no pixel of the image and no position
+    gradient (the layers it empties reach neither), only the inverse-UV
+    winners of the texture gradients."""
+    from paper_2204_01386_amd.pipeline import Step, make_target
+    out = {}
+    for band in (True, False):
+        s = scenes.config3(n_views=3, subdiv=4, H=128, tex_size=256, env_size=16)
+        s.extra["band"] = band
+        st = Step(s, target=make_target(s))
+        st.run()
+        torch.cuda.synchronize()
+        out[band] = (host(st.rgba()), host(st.tri_id), {k: host(v).copy() for k, v in st.grads().items()})
+    (img_b, tid_b, g_b), (img_f, tid_f, g_f) = out[True], out[False]
+    assert (tid_b != tid_f).any() and (tid_b >= 0).sum() < (tid_f >= 0).sum()
+    assert np.array_equal(img_b, img_f)
+    assert_grad_close(g_b["pos"], g_f["pos"], tol=1e-6, what="position gradient, band vs full")
+
+
+@pytest.mark.parametrize("blend,K,r,band", [("aa", 1, 2 / 128, True), ("aa", 2, 2 / 128, False),
+                                            ("softras", 3, 0.02, True), ("hsr", 2, 0.01, True),
+                                            ("hsr", 3, 0.02, False)])
+def test_step_blend_settings(B, blend, K, r, band):
     """The blend's other settings (§3.4.3) through the whole step against the
-    oracle: anti-aliasing (edge mask = the silhouette boundary, K = 1) and
-    SoftRas-like (every pixel blended), beside the paper's own setting."""
-    _compare_step(scenes.fit_scene(subdiv=3, H=128, K=K, r=r, blend=blend))
+    oracle: anti-aliasing (edge mask = the silhouette boundary) and
+    SoftRas-like (every pixel blended), beside the paper's own setting, in
+    the edge-band and the full form of the layers."""
+    s = scenes.fit_scene(subdiv=3, H=128, K=K, r=r, blend=blend)
+    s.extra["band"] = band
+    _compare_step(s)
 
 
 @pytest.mark.parametrize("concurrent", [False, "index", True])
