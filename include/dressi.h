@@ -110,10 +110,22 @@ int dressi_check_status(dressi_ctx *ctx, int64_t *needed, void *stream);
  *   layers;
  * DRESSI_TUNE_HYBRID_WEIGHT: for strategy 2, the cost of a pixel-parallel
  *   triangle step relative to a triangle-parallel pixel step, in sixteenths
- *   (1..1024, default 24). */
+ *   (1..1024, default 24).
+ * DRESSI_TUNE_EMPTY_SLOTS: 0 (default) = per-fragment outputs are fully
+ *   overwritten, with zeros at empty fragment slots (tri_id < 0); 1 = the
+ *   entries of empty slots are left unwritten (undefined) by
+ *   dressi_interpolate (out), dressi_texture (out), dressi_shade (color,
+ *   dir), dressi_softras_bwd (grad_layer_color, grad_dist),
+ *   dressi_shade_bwd (every member), dressi_texture_bwd (grad_coord) and
+ *   dressi_interpolate_bwd (grad_bary).  Every entry point reads those
+ *   outputs only at non-empty slots, so a pipeline built from them gets the
+ *   same results either way and skips the zero stores (most slots of the
+ *   deeper layers are empty).  Changes which bytes are written, never a
+ *   value at a non-empty slot. */
 #define DRESSI_TUNE_BIN_CAPACITY 1
 #define DRESSI_TUNE_HARD_RASTER 2
 #define DRESSI_TUNE_HYBRID_WEIGHT 3
+#define DRESSI_TUNE_EMPTY_SLOTS 4
 int dressi_tune(dressi_ctx *ctx, int key, int64_t value);
 
 /* Kernel timing for measurement: while on, every kernel launch of the library

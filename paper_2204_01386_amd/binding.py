@@ -26,7 +26,7 @@ if not os.path.exists(LIB_PATH):
 _lib = C.CDLL(LIB_PATH)
 
 TEX_2D, TEX_CUBE, TEX_2D_ARRAY = 0, 1, 2
-TUNE_BIN_CAPACITY, TUNE_HARD_RASTER, TUNE_HYBRID_WEIGHT = 1, 2, 3
+TUNE_BIN_CAPACITY, TUNE_HARD_RASTER, TUNE_HYBRID_WEIGHT, TUNE_EMPTY_SLOTS = 1, 2, 3, 4
 WRAP_REPEAT, WRAP_CLAMP = 0, 1
 BLEND_HSR, BLEND_AA, BLEND_SOFTRAS, BLEND_HARD = 0, 1, 2, 3
 

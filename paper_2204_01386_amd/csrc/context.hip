@@ -135,6 +135,10 @@ extern "C" int dressi_tune(dressi_ctx *ctx, int key, int64_t value) {
         if (value < 1 || value > 1024) return dressi_fail(ctx, DRESSI_EINVAL, "tune: hybrid weight is 1..1024");
         ctx->hybrid_weight = (int)value;
         return DRESSI_OK;
+    case DRESSI_TUNE_EMPTY_SLOTS:
+        if (value != 0 && value != 1) return dressi_fail(ctx, DRESSI_EINVAL, "tune: empty slots is 0 or 1");
+        ctx->skip_empty = (int)value;
+        return DRESSI_OK;
     default:
         return dressi_fail(ctx, DRESSI_EINVAL, "tune: unknown key");
     }

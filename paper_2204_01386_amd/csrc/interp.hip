@@ -20,14 +20,16 @@ template <int CC>
 __global__ void __launch_bounds__(256)
     k_interp(const float *__restrict__ attr, int Ba, int Va, int C_, const int32_t *__restrict__ attr_tris,
              int T, const int32_t *__restrict__ tri_id, const float2 *__restrict__ bary, int64_t per_view,
-             int64_t n, float *__restrict__ out) {
+             int64_t n, float *__restrict__ out, int skip_empty) {
     extern __shared__ float stage[];   // [256 * C]
     const int C = CC > 0 ? CC : C_;
     const int64_t o0 = (int64_t)blockIdx.x * 256;
     const int64_t o = o0 + threadIdx.x;
     float *y = stage + threadIdx.x * C;
+    const int t = o < n ? tri_id[o] : -1;
+    // empty fragments left unwritten: a block without a fragment stores nothing
+    if (skip_empty && !__syncthreads_or(t >= 0)) return;
     if (o < n) {
-        int t = tri_id[o];
         int v0 = -1, v1 = -1, v2 = -1;
         if (t >= 0 && t < T) {
             v0 = attr_tris[3 * (int64_t)t];
@@ -69,11 +71,12 @@ __global__ void __launch_bounds__(256)
 __global__ void k_interp_wide(const float *__restrict__ attr, int Ba, int Va, int C,
                               const int32_t *__restrict__ attr_tris, int T, const int32_t *__restrict__ tri_id,
                               const float2 *__restrict__ bary, int64_t per_view, int64_t n,
-                              float *__restrict__ out) {
+                              float *__restrict__ out, int skip_empty) {
     int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (o >= n) return;
     float *y = out + o * C;
     int t = tri_id[o];
+    if (skip_empty && t < 0) return;
     int v0 = -1, v1 = -1, v2 = -1;
     if (t >= 0 && t < T) {
         v0 = attr_tris[3 * (int64_t)t];
@@ -119,16 +122,16 @@ extern "C" int dressi_interpolate(dressi_ctx *ctx, const float *attr, int Ba, in
     const float2 *b2 = reinterpret_cast<const float2 *>(bary);
     const int64_t pv = (int64_t)K * H * W;
     switch (C) {
-    case 2: DR_LAUNCH("k_interp", (k_interp<2>), g, 256, sh, st, attr, Ba, Va, C, attr_tris, T, tri_id, b2, pv, n, out); break;
-    case 6: DR_LAUNCH("k_interp", (k_interp<6>), g, 256, sh, st, attr, Ba, Va, C, attr_tris, T, tri_id, b2, pv, n, out); break;
-    case 9: DR_LAUNCH("k_interp", (k_interp<9>), g, 256, sh, st, attr, Ba, Va, C, attr_tris, T, tri_id, b2, pv, n, out); break;
+    case 2: DR_LAUNCH("k_interp", (k_interp<2>), g, 256, sh, st, attr, Ba, Va, C, attr_tris, T, tri_id, b2, pv, n, out, ctx->skip_empty); break;
+    case 6: DR_LAUNCH("k_interp", (k_interp<6>), g, 256, sh, st, attr, Ba, Va, C, attr_tris, T, tri_id, b2, pv, n, out, ctx->skip_empty); break;
+    case 9: DR_LAUNCH("k_interp", (k_interp<9>), g, 256, sh, st, attr, Ba, Va, C, attr_tris, T, tri_id, b2, pv, n, out, ctx->skip_empty); break;
     default:
         if (C <= 32)
             DR_LAUNCH("k_interp", (k_interp<0>), g, 256, sh, st, attr, Ba, Va, C, attr_tris, T, tri_id, b2, pv, n,
-                      out);
+                      out, ctx->skip_empty);
         else
             DR_LAUNCH("k_interp", (k_interp_wide), g, 256, 0, st, attr, Ba, Va, C, attr_tris, T, tri_id, b2, pv, n,
-                      out);
+                      out, ctx->skip_empty);
         break;
     }
     return dressi_launch_check(ctx, "interpolate");
@@ -139,10 +142,11 @@ __global__ void k_interp_bwd_bary(const float *__restrict__ attr, int Ba, int Va
                                   const int32_t *__restrict__ attr_tris, int T,
                                   const int32_t *__restrict__ tri_id, int64_t per_view, int64_t n,
                                   const float *__restrict__ grad_out, const float2 *__restrict__ gb_in,
-                                  float2 *__restrict__ grad_bary) {
+                                  float2 *__restrict__ grad_bary, int skip_empty) {
     int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (o >= n) return;
     int t = tri_id[o];
+    if (skip_empty && t < 0) return;
     int v0 = -1, v1 = -1, v2 = -1;
     if (t >= 0 && t < T) {
         v0 = attr_tris[3 * (int64_t)t];
@@ -197,7 +201,7 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX)
                       const int32_t *__restrict__ attr_tris, int T, const int32_t *__restrict__ tri_id,
                       const float2 *__restrict__ bary, int K, int H, int W, int ntx, int nt, FragLists fl,
                       const float *__restrict__ grad_out, const float2 *__restrict__ gb_in,
-                      float2 *__restrict__ grad_bary, float *__restrict__ partial) {
+                      float2 *__restrict__ grad_bary, float *__restrict__ partial, int skip_empty) {
     extern __shared__ float vals[];   // [K*256][ib_stride(C)]
     if (CC > 0) C = CC;
     // several views: XCD-aware order (each XCD whole views); one view keeps the
@@ -220,6 +224,7 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX)
                 v1 = attr_tris[3 * (int64_t)t + 1];
                 v2 = attr_tris[3 * (int64_t)t + 2];
             }
+            if (skip_empty && t < 0) continue;
             bool ok = v0 >= 0 && v0 < Va && v1 >= 0 && v1 < Va && v2 >= 0 && v2 < Va;
             float2 acc = gb_in ? gb_in[o] : make_float2(0.0f, 0.0f);
             const float *g = grad_out + o * C;
@@ -435,16 +440,20 @@ extern "C" int dressi_interpolate_bwd(dressi_ctx *ctx, const float *attr, int Ba
             float2 *gbo = reinterpret_cast<float2 *>(grad_bary);
             if (al8 && C == 6)
                 DR_LAUNCH("k_interp_bwd_tile", (k_interp_bwd_tile<6>), B * nt, DRESSI_TILE_PIX, lds, st, attr, Ba,
-                          Va, C, attr_tris, T, tri_id, b2, K, H, W, ntx, nt, fl, grad_out, gbi, gbo, part);
+                          Va, C, attr_tris, T, tri_id, b2, K, H, W, ntx, nt, fl, grad_out, gbi, gbo, part,
+                          ctx->skip_empty);
             else if (al8 && C == 2)
                 DR_LAUNCH("k_interp_bwd_tile", (k_interp_bwd_tile<2>), B * nt, DRESSI_TILE_PIX, lds, st, attr, Ba,
-                          Va, C, attr_tris, T, tri_id, b2, K, H, W, ntx, nt, fl, grad_out, gbi, gbo, part);
+                          Va, C, attr_tris, T, tri_id, b2, K, H, W, ntx, nt, fl, grad_out, gbi, gbo, part,
+                          ctx->skip_empty);
             else if (C == 9)
                 DR_LAUNCH("k_interp_bwd_tile", (k_interp_bwd_tile<9>), B * nt, DRESSI_TILE_PIX, lds, st, attr, Ba,
-                          Va, C, attr_tris, T, tri_id, b2, K, H, W, ntx, nt, fl, grad_out, gbi, gbo, part);
+                          Va, C, attr_tris, T, tri_id, b2, K, H, W, ntx, nt, fl, grad_out, gbi, gbo, part,
+                          ctx->skip_empty);
             else
                 DR_LAUNCH("k_interp_bwd_tile", (k_interp_bwd_tile<0>), B * nt, DRESSI_TILE_PIX, lds, st, attr, Ba,
-                          Va, C, attr_tris, T, tri_id, b2, K, H, W, ntx, nt, fl, grad_out, gbi, gbo, part);
+                          Va, C, attr_tris, T, tri_id, b2, K, H, W, ntx, nt, fl, grad_out, gbi, gbo, part,
+                          ctx->skip_empty);
         }
         const int64_t nv = (int64_t)Ba * Va, gv = (nv * IBV_LANES + 255) / 256;
         if (C == 6)
@@ -464,7 +473,8 @@ extern "C" int dressi_interpolate_bwd(dressi_ctx *ctx, const float *attr, int Ba
     } else if (grad_bary && n > 0) {
         DR_LAUNCH("k_interp_bwd_bary", (k_interp_bwd_bary), (int)((n + 255) / 256), 256, 0, st,
                   attr, Ba, Va, C, attr_tris, T, tri_id, (int64_t)K * H * W, n, grad_out,
-                  reinterpret_cast<const float2 *>(grad_bary_in), reinterpret_cast<float2 *>(grad_bary));
+                  reinterpret_cast<const float2 *>(grad_bary_in), reinterpret_cast<float2 *>(grad_bary),
+                  ctx->skip_empty);
     }
     return dressi_launch_check(ctx, "interpolate_bwd");
 }

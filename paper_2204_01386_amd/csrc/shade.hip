@@ -388,10 +388,11 @@ __device__ __forceinline__ void shade_forward(int mode, const dressi_frag_in &in
 
 __global__ void k_shade(int mode, dressi_frag_in in, const float *__restrict__ eye,
                         const int32_t *__restrict__ tri_id, int64_t N, int64_t Npv,
-                        float *__restrict__ color, float *__restrict__ dir) {
+                        float *__restrict__ color, float *__restrict__ dir, int skip_empty) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
     if (tri_id[i] < 0) {
+        if (skip_empty) return;
         if (color) { color[3 * i] = 0.0f; color[3 * i + 1] = 0.0f; color[3 * i + 2] = 0.0f; }
         if (dir) { dir[3 * i] = 0.0f; dir[3 * i + 1] = 0.0f; dir[3 * i + 2] = 0.0f; }
         return;
@@ -421,11 +422,12 @@ __device__ __forceinline__ void st3(float *p, int64_t i, int stride, d3 v) {
 __global__ void k_shade_bwd(int mode, dressi_frag_in in, const float *__restrict__ eye,
                             const int32_t *__restrict__ tri_id, int64_t N, int64_t Npv,
                             const float *__restrict__ grad_color, const float *__restrict__ grad_dir,
-                            dressi_frag_grad gr) {
+                            dressi_frag_grad gr, int skip_empty) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
     const d3 Z{0.0, 0.0, 0.0};
     if (tri_id[i] < 0) {
+        if (skip_empty) return;
         if (gr.normal) st3(gr.normal, i, gr.normal_stride, Z);
         if (gr.pos) st3(gr.pos, i, gr.pos_stride, Z);
         if (gr.tangent) st3(gr.tangent, i, gr.tangent_stride, Z);
@@ -525,7 +527,7 @@ extern "C" int dressi_shade(dressi_ctx *ctx, int mode, const dressi_frag_in *in,
     if (color && mode == DRESSI_SHADE_PHONG_ENV && !in->env)
         return dressi_fail(ctx, DRESSI_EINVAL, "shade: PHONG_ENV colour needs the environment sample");
     DR_LAUNCH("k_shade", (k_shade), (int)((N + 255) / 256), 256, 0, (hipStream_t)stream, mode, *in, eye, tri_id, N, Npv,
-                                                                      color, dir);
+                                                                      color, dir, ctx->skip_empty);
     return dressi_launch_check(ctx, "shade");
 }
 
@@ -541,7 +543,7 @@ extern "C" int dressi_shade_bwd(dressi_ctx *ctx, int mode, const dressi_frag_in 
     if (mode == DRESSI_SHADE_PHONG_ENV && !in->env && (grad->albedo || grad->normal || grad->pos))
         return dressi_fail(ctx, DRESSI_EINVAL, "shade_bwd: PHONG_ENV needs the environment sample");
     DR_LAUNCH("k_shade_bwd", (k_shade_bwd), (int)((N + 255) / 256), 256, 0, (hipStream_t)stream, mode, *in, eye, tri_id, N, Npv,
-                                                                          grad_color, grad_dir, *grad);
+                                                                          grad_color, grad_dir, *grad, ctx->skip_empty);
     return dressi_launch_check(ctx, "shade_bwd");
 }
 

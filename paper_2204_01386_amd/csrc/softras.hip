@@ -151,7 +151,7 @@ __global__ void k_blend_bwd(const float *__restrict__ color, const float *__rest
                             const int32_t *__restrict__ tri_id, int B, int H, int W, int Cc,
                             float inv_sigma, const uint8_t *__restrict__ edge,
                             const float *__restrict__ grad_color, const float *__restrict__ grad_sil,
-                            float *__restrict__ grad_layer, float *__restrict__ grad_dist) {
+                            float *__restrict__ grad_layer, float *__restrict__ grad_dist, int skip_empty) {
     int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t N = (int64_t)H * W;
     if (gid >= (int64_t)B * N) return;
@@ -165,6 +165,7 @@ __global__ void k_blend_bwd(const float *__restrict__ color, const float *__rest
 #pragma unroll
         for (int k = 0; k < K; k++) {
             int64_t o = o1 + (int64_t)k * N;
+            if (skip_empty && tri_id[o] < 0) continue;
             float *gl = grad_layer + o * Cc;
             for (int c = 0; c < Cc; c++) gl[c] = (k == 0 && sh) ? gc[c] : 0.0f;
             if (grad_dist) grad_dist[o] = 0.0f;
@@ -205,7 +206,7 @@ __global__ void k_blend_bwd(const float *__restrict__ color, const float *__rest
             if (S[k]) {
                 grad_layer[o * Cc + c] = gc[c] * w[k] * inv;
                 gw[k] += gc[c] * (color[o * Cc + c] - ic) * inv;
-            } else {
+            } else if (!skip_empty) {
                 grad_layer[o * Cc + c] = 0.0f;
             }
         }
@@ -214,7 +215,7 @@ __global__ void k_blend_bwd(const float *__restrict__ color, const float *__rest
 #pragma unroll
         for (int k = 0; k < K; k++) {
             int64_t o = o1 + (int64_t)k * N;
-            grad_dist[o] = S[k] ? gw[k] * w[k] * q[k] * inv_sigma : 0.0f;
+            if (S[k] || !skip_empty) grad_dist[o] = S[k] ? gw[k] * w[k] * q[k] * inv_sigma : 0.0f;
         }
     }
 }
@@ -367,6 +368,6 @@ extern "C" int dressi_softras_bwd(dressi_ctx *ctx, const float *color, const flo
     int g = (int)((n + 255) / 256);
     KDISPATCH(K, DR_LAUNCH("k_blend_bwd", (k_blend_bwd<KK>), g, 256, 0, st, color, dist, tri_id, B, H, W, Cc, inv_sigma,
                                                      edge_mask, grad_color, grad_sil,
-                                                     grad_layer_color, grad_dist));
+                                                     grad_layer_color, grad_dist, ctx->skip_empty));
     return dressi_launch_check(ctx, "softras_bwd");
 }

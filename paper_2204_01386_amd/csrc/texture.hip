@@ -148,9 +148,10 @@ __device__ __forceinline__ void stv(float *__restrict__ p, const float *v, int C
 template <int CT>
 __global__ void __launch_bounds__(256)
     k_tex_fwd(const float *__restrict__ tex, dressi_tex_desc td, const float *__restrict__ coord,
-              const int32_t *__restrict__ tri_id, int64_t n, float *__restrict__ out) {
+              const int32_t *__restrict__ tri_id, int64_t n, float *__restrict__ out, int skip_empty) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    if (skip_empty && tri_id && tri_id[i] < 0) return;
     const int Ct = CT > 0 ? CT : td.Ct;
     const int cd = td.kind == DRESSI_TEX_CUBE ? 3 : 2;
     float *y = out + i * Ct;
@@ -184,7 +185,7 @@ __global__ void __launch_bounds__(256)
     k_tex_bwd_pixel(const float *__restrict__ tex, dressi_tex_desc td,
                                 const float *__restrict__ coord, const int32_t *__restrict__ tri_id,
                                 int64_t npix, int S, const float *__restrict__ grad_out,
-                                float *__restrict__ grad_coord, int32_t *__restrict__ inv) {
+                                float *__restrict__ grad_coord, int32_t *__restrict__ inv, int skip_empty) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= (int64_t)S * npix) return;
     const int Ct = CT > 0 ? CT : td.Ct;
@@ -211,7 +212,7 @@ __global__ void __launch_bounds__(256)
         int64_t cells = (int64_t)tex_faces(td) * td.Ht * td.Wt;
         atomicMax(&inv[(int64_t)s * cells + ((int64_t)t.face * td.Ht + cy) * td.Wt + cx], pix);
     }
-    if (!grad_coord) return;
+    if (!grad_coord || (skip_empty && !covered)) return;
     float *gc = grad_coord + i * cd;
     if (!t.ok) {
         for (int j = 0; j < cd; j++) gc[j] = 0.0f;
@@ -491,10 +492,10 @@ extern "C" int dressi_texture(dressi_ctx *ctx, const float *tex, const dressi_te
     hipStream_t st = (hipStream_t)stream;
     const int g = (int)((n + 255) / 256);
     switch (aligned16(tex, out) ? td->Ct : 0) {
-    case 3: DR_LAUNCH("k_tex_fwd", (k_tex_fwd<3>), g, 256, 0, st, tex, *td, coord, tri_id, n, out); break;
-    case 4: DR_LAUNCH("k_tex_fwd", (k_tex_fwd<4>), g, 256, 0, st, tex, *td, coord, tri_id, n, out); break;
-    case 8: DR_LAUNCH("k_tex_fwd", (k_tex_fwd<8>), g, 256, 0, st, tex, *td, coord, tri_id, n, out); break;
-    default: DR_LAUNCH("k_tex_fwd", (k_tex_fwd<0>), g, 256, 0, st, tex, *td, coord, tri_id, n, out); break;
+    case 3: DR_LAUNCH("k_tex_fwd", (k_tex_fwd<3>), g, 256, 0, st, tex, *td, coord, tri_id, n, out, ctx->skip_empty); break;
+    case 4: DR_LAUNCH("k_tex_fwd", (k_tex_fwd<4>), g, 256, 0, st, tex, *td, coord, tri_id, n, out, ctx->skip_empty); break;
+    case 8: DR_LAUNCH("k_tex_fwd", (k_tex_fwd<8>), g, 256, 0, st, tex, *td, coord, tri_id, n, out, ctx->skip_empty); break;
+    default: DR_LAUNCH("k_tex_fwd", (k_tex_fwd<0>), g, 256, 0, st, tex, *td, coord, tri_id, n, out, ctx->skip_empty); break;
     }
     return dressi_launch_check(ctx, "texture");
 }
@@ -503,7 +504,7 @@ extern "C" int dressi_texture(dressi_ctx *ctx, const float *tex, const dressi_te
 // map (cleared to -1 first) and, when grad_coord is given, writes d out / d coord.
 static void tex_bwd_pixels(const float *tex, const dressi_tex_desc &td, const float *coord,
                            const int32_t *tri_id, int64_t npix, int S, const float *grad_out,
-                           float *grad_coord, int32_t *inv, hipStream_t st) {
+                           float *grad_coord, int32_t *inv, hipStream_t st, int skip_empty = 0) {
     const int64_t n = (int64_t)S * npix;
     // cleared for every slice, also when slices are empty: the gather reads them all
     if (inv && S > 0) dressi_fill_i32(inv, -1, (int64_t)tex_faces(td) * td.Ht * td.Wt * S, st);
@@ -511,13 +512,13 @@ static void tex_bwd_pixels(const float *tex, const dressi_tex_desc &td, const fl
     const int g = (int)((n + 255) / 256);
     switch (grad_coord && aligned16(tex, grad_out) ? td.Ct : 0) {
     case 3: DR_LAUNCH("k_tex_bwd_pixel", (k_tex_bwd_pixel<3>), g, 256, 0, st, tex, td, coord, tri_id, npix, S,
-                      grad_out, grad_coord, inv); break;
+                      grad_out, grad_coord, inv, skip_empty); break;
     case 4: DR_LAUNCH("k_tex_bwd_pixel", (k_tex_bwd_pixel<4>), g, 256, 0, st, tex, td, coord, tri_id, npix, S,
-                      grad_out, grad_coord, inv); break;
+                      grad_out, grad_coord, inv, skip_empty); break;
     case 8: DR_LAUNCH("k_tex_bwd_pixel", (k_tex_bwd_pixel<8>), g, 256, 0, st, tex, td, coord, tri_id, npix, S,
-                      grad_out, grad_coord, inv); break;
+                      grad_out, grad_coord, inv, skip_empty); break;
     default: DR_LAUNCH("k_tex_bwd_pixel", (k_tex_bwd_pixel<0>), g, 256, 0, st, tex, td, coord, tri_id, npix,
-                       S, grad_out, grad_coord, inv); break;
+                       S, grad_out, grad_coord, inv, skip_empty); break;
     }
 }
 
@@ -573,7 +574,7 @@ extern "C" int dressi_texture_bwd(dressi_ctx *ctx, const float *tex, const dress
         inv = at<int32_t>(ctx->scratch, o_inv);
         part = at<float>(ctx->scratch, o_part);
     }
-    tex_bwd_pixels(tex, *td, coord, tri_id, npix, S, grad_out, grad_coord, inv, st);
+    tex_bwd_pixels(tex, *td, coord, tri_id, npix, S, grad_out, grad_coord, inv, st, ctx->skip_empty);
     if (grad_tex) tex_gather(*td, coord, tri_id, npix, S, inv, grad_out, part, grad_tex, st);
     return dressi_launch_check(ctx, "texture_bwd");
 }

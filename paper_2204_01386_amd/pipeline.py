@@ -14,6 +14,7 @@ one inverse-UV gather serve both, with aligned float4 texel rows.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes as C
 import math
 
@@ -64,6 +65,23 @@ class _TwoStreams:
 
     concurrent = False
     _forked = False
+    # every consumer in a step reads per-fragment buffers only at non-empty
+    # slots, so the step's calls leave the entries of empty slots unwritten
+    skip_empty = True
+
+    @contextlib.contextmanager
+    def _sparse(self):
+        """Sets DRESSI_TUNE_EMPTY_SLOTS on the step's contexts for the calls
+        inside (a captured graph keeps the setting it was recorded with) and
+        restores the default after."""
+        ctxs = (self.ctx, self.ctx2) if self.skip_empty else ()
+        for c in ctxs:
+            c.tune(Bd.TUNE_EMPTY_SLOTS, 1)
+        try:
+            yield
+        finally:
+            for c in ctxs:
+                c.tune(Bd.TUNE_EMPTY_SLOTS, 0)
 
     def _init_streams(self, dev):
         self._aux = None
@@ -294,6 +312,10 @@ class Step(_TwoStreams):
         return C.c_void_p(torch.cuda.current_stream().cuda_stream)
 
     def forward(self):
+        with self._sparse():
+            self._forward()
+
+    def _forward(self):
         h, s = self.ctx.handle, self._s()
         B, V, T, H, W, K = self.B, self.V, self.T, self.H, self.W, self.K
         ck = self._chk
@@ -334,6 +356,10 @@ class Step(_TwoStreams):
                                self._s()), "loss")
 
     def backward(self):
+        with self._sparse():
+            self._backward()
+
+    def _backward(self):
         h, s = self.ctx.handle, self._s()
         B, V, T, H, W, K = self.B, self.V, self.T, self.H, self.W, self.K
         ck = self._chk
@@ -453,6 +479,10 @@ class TextureStep:
                                         st.H, st.W, _p(self.inv), st._s()), "invuv_build")
 
     def forward(self):
+        with self.st._sparse():
+            self._forward()
+
+    def _forward(self):
         st = self.st
         h, s, ck = st.ctx.handle, st._s(), st._chk
         B, K, H, W = st.B, st.K, st.H, st.W
@@ -472,6 +502,10 @@ class TextureStep:
         self.st.loss_and_grad()
 
     def backward(self):
+        with self.st._sparse():
+            self._backward()
+
+    def _backward(self):
         st = self.st
         h, s, ck = st.ctx.handle, st._s(), st._chk
         B, K, H, W = st.B, st.K, st.H, st.W
@@ -691,6 +725,10 @@ class BatchStep(_TwoStreams):
         raise RuntimeError("tile bins still overflow after growing them")
 
     def forward(self):
+        with self._sparse():
+            self._forward()
+
+    def _forward(self):
         h, st = self.ctx.handle, self._s()
         H, W, V, T, ck = self.H, self.W, self.V, self.T, self._chk
         self._fork("attrs")
@@ -719,6 +757,10 @@ class BatchStep(_TwoStreams):
                                       _p(self.g_sil), self._s()), "loss")
 
     def backward(self):
+        with self._sparse():
+            self._backward()
+
+    def _backward(self):
         h, st = self.ctx.handle, self._s()
         H, W, V, T, ck, Ct = self.H, self.W, self.V, self.T, self._chk, self.Ct
         ck(_lib.dressi_softras_bwd(h, _p(self.layer_color), None, _p(self.tri_id), 1, 1, H, W, 3, 1.0, _p(self.E),

@@ -261,3 +261,102 @@ def test_step_deterministic_and_graph_replay(B, concurrent):
         for k, v in st.grads().items():
             assert np.array_equal(host(v), ref[k]), f"replay {rep}: {k} differs from eager"
     assert B.context().check_status() == 0
+
+
+@pytest.mark.parametrize("which", ["config3_band", "config3_full", "config1"])
+def test_step_empty_slots_skipped_changes_no_result(B, which):
+    """The step leaves per-fragment outputs of empty slots unwritten
+    (DRESSI_TUNE_EMPTY_SLOTS); its image, loss and every gradient are bitwise
+    those of the same step writing zeros there, eager and in graph replays."""
+    from paper_2204_01386_amd.pipeline import Step, make_target
+    if which == "config1":
+        s = scenes.config1()
+    else:
+        s = scenes.config3(n_views=3, subdiv=4, H=128, tex_size=256, env_size=16)
+        s.extra["band"] = which == "config3_band"
+    out = {}
+    for skip in (False, True):
+        st = Step(s, target=make_target(s))
+        st.skip_empty = skip
+        st.run()
+        torch.cuda.synchronize()
+        out[skip] = (host(st.rgba()), host(st.loss), {k: host(v).copy() for k, v in st.grads().items()})
+        if skip:
+            g = torch.cuda.CUDAGraph()
+            side = torch.cuda.Stream()
+            side.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(side):
+                st.run()
+            torch.cuda.current_stream().wait_stream(side)
+            torch.cuda.synchronize()
+            with torch.cuda.graph(g):
+                st.run()
+            for v in st.grads().values():
+                v.fill_(5.0)
+            g.replay()
+            torch.cuda.synchronize()
+            for k, v in st.grads().items():
+                assert np.array_equal(host(v), out[False][2][k]), f"replay: {k} differs"
+    assert np.array_equal(out[True][0], out[False][0])
+    assert np.array_equal(out[True][1], out[False][1])
+    for k in out[False][2]:
+        assert np.array_equal(out[True][2][k], out[False][2][k]), f"{k} differs"
+    assert B.context().check_status() == 0
+
+
+def test_empty_slots_knob_entry_points(B):
+    """With DRESSI_TUNE_EMPTY_SLOTS = 1 the per-fragment entry points leave
+    the entries of empty slots as they were and write the same bits at every
+    non-empty slot; the knob is reset afterwards."""
+    import ctypes as C
+    from paper_2204_01386_amd.binding import _lib, _ptr, _stream
+    s = scenes.config3(n_views=2, subdiv=3, H=64, tex_size=64, env_size=8)
+    pc = oracle.transform_f32(s.pos, s.mvp)
+    tid_o, _, bary_o, dist_o = oracle.rasterize(pc, s.tris, 64, 64, K=3, r=0.05)
+    tid, bary = dev(tid_o), dev(bary_o.astype(np.float32))
+    empty = tid_o < 0
+    assert empty.any() and (~empty).any()
+    ctx = B.context()
+    Bv, K, H, W = tid_o.shape
+    rng = np.random.default_rng(2)
+    attr = dev(rng.standard_normal((s.pos.shape[0], 6)).astype(np.float32))
+
+    def interp(skip, sentinel):
+        out = torch.full((Bv, K, H, W, 6), sentinel, device="cuda")
+        ctx.tune(B.TUNE_EMPTY_SLOTS, skip)
+        try:
+            ctx.check(_lib.dressi_interpolate(ctx.handle, _ptr(attr), 1, attr.shape[0], 6, _ptr(dev(s.tris)),
+                                              s.tris.shape[0], _ptr(tid), _ptr(bary), Bv, K, H, W, _ptr(out),
+                                              _stream()), "interpolate")
+        finally:
+            ctx.tune(B.TUNE_EMPTY_SLOTS, 0)
+        return host(out)
+    full, sparse = interp(0, 7.0), interp(1, 7.0)
+    assert (full[empty] == 0).all()
+    # undefined there: a block that stores some fragments also stores its
+    # empty rows (zeros); a block of empty slots stores nothing
+    assert np.isin(sparse[empty], (0.0, 7.0)).all() and (sparse[empty] == 7.0).mean() > 0.2
+    assert np.array_equal(full[~empty], sparse[~empty])
+    # the knob is back at its default: zeros again
+    assert (host(B.dressi_interpolate(attr, dev(s.tris), tid, bary))[empty] == 0).all()
+    # the other entry points: same bits at non-empty slots
+    uv = dev(oracle.interpolate_f32(s.uv, s.uv_tris, tid_o, bary_o.astype(np.float32)))
+    tex = dev(s.tex)
+    gout = dev(rng.standard_normal((Bv, K, H, W, 4)).astype(np.float32))
+    res = {}
+    for skip in (0, 1):
+        ctx.tune(B.TUNE_EMPTY_SLOTS, skip)
+        try:
+            smp = B.dressi_texture(tex, uv, tid)
+            _, gc = B.dressi_texture_bwd(tex, uv, tid, gout, need_tex=False)
+            _, gb = B.dressi_interpolate_bwd(dev(s.uv), dev(s.uv_tris), tid, bary, gc.contiguous(), need_attr=False)
+            col = dev(rng.random((Bv, K, H, W, 3)).astype(np.float32)) if skip == 0 else col
+            d32 = dev(dist_o.astype(np.float32))
+            _, _, E = B.dressi_softras(col, d32, tid, 0.05 / 7, 0.05)
+            gl, gd = B.dressi_softras_bwd(col, d32, tid, 0.05 / 7, E,
+                                          dev(np.ones((Bv, H, W, 3), np.float32)), dev(np.ones((Bv, H, W), np.float32)))
+            res[skip] = [host(smp), host(gc), host(gb), host(gl), host(gd)]
+        finally:
+            ctx.tune(B.TUNE_EMPTY_SLOTS, 0)
+    for a, b_ in zip(res[0], res[1]):
+        assert np.array_equal(a[~empty], b_[~empty])
