@@ -280,10 +280,22 @@ int dressi_texture(dressi_ctx *ctx, const float *tex, const dressi_tex_desc *td,
  * every slice, the kept pixel's gradient times that pixel's bilinear weight on
  * the texel.  Integer atomicMax on pixel indices only, no float atomics; the
  * sum runs over slices, then cells in row-major order.  Either output may be
- * NULL.  Needs Ht, Wt >= 3 for repeat wrap. */
+ * NULL.  Needs Ht, Wt >= 3 for repeat wrap.
+ * frame: 0 = no jitter (as above).  frame >= 1 moves the sampling positions
+ * of the inverse UV by the frame's quasi-random offset (§3.3.2: a Sobol
+ * sequence, so that the pixel a cell keeps changes from frame to frame):
+ * o = Sobol(frame) - 1/2 in both axes (the 2-D Sobol point of index frame,
+ * base-2 radical inverse and the direction numbers of x + 1, 24 bits).  A
+ * covered pixel registers the coordinate and the gradient sampled
+ * bilinearly from this slice's coord and grad_out planes at its centre plus
+ * o (in float, ((w00 v00 + w01 v01) + w10 v10) + w11 v11), but only when
+ * the four pixels sampled are covered pixels of the image; the gather then
+ * uses those samples.  grad_coord does not depend on frame.  2-D and cube
+ * textures (EINVAL for arrays). */
 int dressi_texture_bwd(dressi_ctx *ctx, const float *tex, const dressi_tex_desc *td,
                        const float *coord, const int32_t *tri_id, int S, int H, int W,
-                       const float *grad_out, float *grad_tex, float *grad_coord, void *stream);
+                       const float *grad_out, uint32_t frame, float *grad_tex, float *grad_coord,
+                       void *stream);
 
 /* The two halves of the texture gradient of dressi_texture_bwd, for a scene
  * whose geometry is held fixed while only textures are optimised (the

@@ -523,3 +523,55 @@ def band_layers(tri_id, hard, bary, dist, delta, mode=BLEND_HSR):
     ba[~keep] = 0.0
     di[~keep] = 0.0
     return tid, hd, ba, di
+
+
+def sobol2(f):
+    """The 2-D Sobol point of index f, to 24 fraction bits.  First
+    coordinate: the base-2 radical inverse of f.  Second: the direction
+    numbers of the primitive polynomial x + 1 (m_1 = 1, m_k = 2 m_(k-1) xor
+    m_(k-1)).  Each coordinate is the xor over the set bits k of f of
+    m_(k+1) / 2^(k+1)."""
+    f = int(f)
+    a = b = 0
+    m = 1
+    for k in range(32):
+        if (f >> k) & 1:
+            a ^= 1 << (31 - k)
+            b ^= m << (31 - k)
+        m = (m << 1) ^ m
+    return (a >> 8) / 16777216.0, (b >> 8) / 16777216.0
+
+
+def jitter_samples(coord, tri_id, grad, frame):
+    """The inverse UV's jittered samples (§3.3.2: the sampling position of
+    each pixel moves by a quasi-random offset per frame, o = Sobol(frame) -
+    1/2 in both axes).  coord [S,H,W,cd] float32, tri_id [S,H,W], grad
+    [S,H,W,Ct].  Every covered pixel whose four bilinear taps around its
+    moved centre are covered pixels of the image registers the coordinate
+    sampled there, ((w00 c00 + w01 c01) + w10 c10) + w11 c11 in float32 (it
+    selects texture cells and taps), and the gradient sampled with the same
+    weights (double).  Returns (coord', tri_id', grad'), tri_id' = -1 where a
+    pixel does not register: the inputs of the unjittered inverse UV."""
+    c = np.asarray(coord, np.float32)
+    tid = np.asarray(tri_id, np.int32)
+    g = np.asarray(grad, np.float64)
+    S, H, W = tid.shape
+    u, v = sobol2(frame)
+    ox, oy = np.float32(u - 0.5), np.float32(v - 0.5)
+    dx, dy = int(np.floor(ox)), int(np.floor(oy))
+    fx, fy = ox - np.float32(dx), oy - np.float32(dy)
+    one = np.float32(1.0)
+    w = [(one - fy) * (one - fx), (one - fy) * fx, fy * (one - fx), fy * fx]
+    ys, xs = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
+    x0, y0 = xs + dx, ys + dy
+    inside = (x0 >= 0) & (y0 >= 0) & (x0 + 1 < W) & (y0 + 1 < H)
+    x0c, y0c = np.clip(x0, 0, W - 2), np.clip(y0, 0, H - 2)
+    taps = [(y0c, x0c), (y0c, x0c + 1), (y0c + 1, x0c), (y0c + 1, x0c + 1)]
+    ok = (tid >= 0) & inside[None]
+    for ty, tx in taps:
+        ok &= tid[:, ty, tx] >= 0
+    jc = w[0] * c[:, taps[0][0], taps[0][1]]
+    for k in range(1, 4):
+        jc = jc + w[k] * c[:, taps[k][0], taps[k][1]]
+    jg = sum(np.float64(w[k]) * g[:, taps[k][0], taps[k][1]] for k in range(4))
+    return jc.astype(np.float32), np.where(ok, tid, -1).astype(np.int32), np.asarray(jg, np.float64)

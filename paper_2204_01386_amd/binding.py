@@ -89,7 +89,7 @@ _SIG = {
     "dressi_interpolate_bwd": [_vp, _vp, _i, _i, _i, _vp, _i, _vp, _vp, _i, _i, _i, _i, _vp, _vp,
                                _vp, _vp, _vp, _vp, _vp],
     "dressi_texture": [_vp, _vp, C.POINTER(TexDesc), _vp, _vp, _i, _i, _i, _vp, _vp],
-    "dressi_texture_bwd": [_vp, _vp, C.POINTER(TexDesc), _vp, _vp, _i, _i, _i, _vp, _vp, _vp, _vp],
+    "dressi_texture_bwd": [_vp, _vp, C.POINTER(TexDesc), _vp, _vp, _i, _i, _i, _vp, C.c_uint32, _vp, _vp, _vp],
     "dressi_ibl_filter": [_vp, _vp, C.POINTER(IblDesc), _vp, _vp, _vp, _vp],
     "dressi_ibl_filter_bwd": [_vp, C.POINTER(IblDesc), _vp, _vp, _vp, _vp, _vp],
     "dressi_brdf_lut": [_vp, _i, _i, _vp, _vp],
@@ -371,7 +371,7 @@ def dressi_texture(tex, coord, tri_id, kind=TEX_2D, wrap_u=WRAP_REPEAT, wrap_v=W
 
 
 def dressi_texture_bwd(tex, coord, tri_id, grad_out, kind=TEX_2D, wrap_u=WRAP_REPEAT,
-                       wrap_v=WRAP_CLAMP, need_tex=True, need_coord=True, tri_layer=None):
+                       wrap_v=WRAP_CLAMP, need_tex=True, need_coord=True, tri_layer=None, frame=0):
     _need(grad_out, torch.float32, "grad_out")
     d = _desc(tex, kind, wrap_u, wrap_v, tri_layer)
     lead = coord.shape[:-1]
@@ -381,7 +381,7 @@ def dressi_texture_bwd(tex, coord, tri_id, grad_out, kind=TEX_2D, wrap_u=WRAP_RE
     gc = torch.empty_like(coord) if need_coord else None
     ctx = context(coord.device.index)
     ctx.check(_lib.dressi_texture_bwd(ctx.handle, _ptr(tex), C.byref(d), _ptr(coord), _ptr(tri_id),
-                                      S, H, W, _ptr(grad_out), _ptr(gt), _ptr(gc), _stream()),
+                                      S, H, W, _ptr(grad_out), int(frame), _ptr(gt), _ptr(gc), _stream()),
               "dressi_texture_bwd")
     return gt, gc
 

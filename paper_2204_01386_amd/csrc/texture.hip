@@ -259,6 +259,107 @@ __global__ void __launch_bounds__(256)
     gc[2] = g3[2];
 }
 
+// Sobol jitter of the inverse UV (§3.3.2: the sampling positions move by a
+// quasi-random offset every frame, so the pixel kept by a texel cell changes
+// from frame to frame).  Frame f moves every pixel centre by o_f = Sobol(f) -
+// 1/2 in both axes; the taps of the moved point are the pixels (x + dx, y +
+// dy) + {0,1}^2 with the fixed weights w of the fractions (fx, fy).  A covered
+// pixel whose four taps are covered pixels of the image registers the
+// coordinate and the gradient sampled there, ((w00 v00 + w01 v01) + w10 v10)
+// + w11 v11 in float; the others do not register.  The moved samples are
+// written to jc [S,H,W,cd] and jg [S,H,W,Ct] at the pixel's index, so the
+// gather reads them exactly where it reads the unmoved ones.
+struct Jitter {
+    int dx, dy;                  // tap offsets (floor of the offset), -1 or 0
+    float w00, w01, w10, w11;    // bilinear weights of the fractions
+};
+
+template <int CT>
+__global__ void __launch_bounds__(256)
+    k_invuv_jitter(dressi_tex_desc td, const float *__restrict__ coord, const int32_t *__restrict__ tri_id,
+                   int H, int W, int S, const float *__restrict__ grad_out, Jitter j, float *__restrict__ jc,
+                   float *__restrict__ jg, int32_t *__restrict__ inv) {
+    const int64_t npix = (int64_t)H * W;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)S * npix || tri_id[i] < 0) return;
+    const int s = (int)(i / npix);
+    const int pix = (int)(i - (int64_t)s * npix);
+    const int y = pix / W, x = pix - y * W;
+    const int x0 = x + j.dx, y0 = y + j.dy;
+    if (x0 < 0 || y0 < 0 || x0 + 1 >= W || y0 + 1 >= H) return;
+    const int64_t o00 = (int64_t)s * npix + (int64_t)y0 * W + x0, o01 = o00 + 1, o10 = o00 + W, o11 = o10 + 1;
+    if (tri_id[o00] < 0 || tri_id[o01] < 0 || tri_id[o10] < 0 || tri_id[o11] < 0) return;
+    const bool cube = td.kind == DRESSI_TEX_CUBE;
+    const int cd = cube ? 3 : 2;
+    const int Ct = CT > 0 ? CT : td.Ct;
+    float c[3];
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        if (k >= cd) break;
+        float v = j.w00 * coord[o00 * cd + k];
+        v = v + j.w01 * coord[o01 * cd + k];
+        v = v + j.w10 * coord[o10 * cd + k];
+        c[k] = v + j.w11 * coord[o11 * cd + k];
+        jc[i * cd + k] = c[k];
+    }
+#pragma unroll
+    for (int k = 0; k < TEX_NC(CT); k++) {
+        if (CT == 0 && k >= Ct) break;
+        float v = j.w00 * grad_out[o00 * Ct + k];
+        v = v + j.w01 * grad_out[o01 * Ct + k];
+        v = v + j.w10 * grad_out[o10 * Ct + k];
+        jg[i * Ct + k] = v + j.w11 * grad_out[o11 * Ct + k];
+    }
+    int f = 0, cx, cy;
+    if (cube) {
+        float u, v, sc, tc, ma;
+        f = cube_face(c[0], c[1], c[2], u, v, sc, tc, ma);
+        if (f < 0) return;
+        cx = cell1d(u, td.Wt, DRESSI_WRAP_CLAMP);
+        cy = cell1d(v, td.Ht, DRESSI_WRAP_CLAMP);
+    } else {
+        cx = cell1d(c[0], td.Wt, td.wrap_u);
+        cy = cell1d(c[1], td.Ht, td.wrap_v);
+    }
+    const int64_t cells = (int64_t)tex_faces(td) * td.Ht * td.Wt;
+    atomicMax(&inv[(int64_t)s * cells + ((int64_t)f * td.Ht + cy) * td.Wt + cx], pix);
+}
+
+// The 2-D Sobol point of index f (f = 0, 1, 2, ...) to 24 bits: the first
+// coordinate is the base-2 radical inverse of f, the second uses the
+// direction numbers m_1 = 1, m_k = 2 m_{k-1} xor m_{k-1} (the primitive
+// polynomial x + 1); each coordinate is the xor, over the set bits k of f,
+// of m_(k+1) / 2^(k+1), truncated to 24 fraction bits (exact in float).
+static void sobol2(uint32_t f, float *u, float *v) {
+    uint32_t a = 0, b = 0, m = 1;
+    for (int k = 0; k < 32; k++) {
+        if ((f >> k) & 1u) {
+            a ^= 1u << (31 - k);
+            b ^= m << (31 - k);
+        }
+        m = (m << 1) ^ m;
+    }
+    *u = (float)(a >> 8) * (1.0f / 16777216.0f);
+    *v = (float)(b >> 8) * (1.0f / 16777216.0f);
+}
+
+static Jitter jitter_of_frame(uint32_t frame) {
+    float u, v;
+    sobol2(frame, &u, &v);
+    const float ox = u - 0.5f, oy = v - 0.5f;   // exact: 24-bit fractions
+    const float flx = floorf(ox), fly = floorf(oy);
+    const float fx = ox - flx, fy = oy - fly;    // exact
+    Jitter j;
+    j.dx = (int)flx;
+    j.dy = (int)fly;
+    const float gx = 1.0f - fx, gy = 1.0f - fy;
+    j.w00 = gy * gx;
+    j.w01 = gy * fx;
+    j.w10 = fy * gx;
+    j.w11 = fy * fx;
+    return j;
+}
+
 // Texture gradient through the inverse UV.  One block of texels (16 columns,
 // 32 rows when one slice is staged at a time, else 16) per workgroup: per slice the cells
 // around the block (a one-cell halo) are staged in LDS
@@ -553,7 +654,7 @@ static int check_grad_tex(dressi_ctx *ctx, const dressi_tex_desc *td, const int3
 
 extern "C" int dressi_texture_bwd(dressi_ctx *ctx, const float *tex, const dressi_tex_desc *td,
                                   const float *coord, const int32_t *tri_id, int S, int H, int W,
-                                  const float *grad_out, float *grad_tex, float *grad_coord,
+                                  const float *grad_out, uint32_t frame, float *grad_tex, float *grad_coord,
                                   void *stream) {
     int rc = check_tex(ctx, tex, td, coord, tri_id, S, H, W);
     if (rc) return rc;
@@ -561,21 +662,52 @@ extern "C" int dressi_texture_bwd(dressi_ctx *ctx, const float *tex, const dress
     if (n > 0 && !grad_out) return dressi_fail(ctx, DRESSI_EINVAL, "texture_bwd: null grad_out");
     if (grad_tex && (rc = check_grad_tex(ctx, td, tri_id, "texture_bwd: the texture gradient needs tri_id")))
         return rc;
+    const bool jit = grad_tex && frame > 0;
+    if (jit && td->kind == DRESSI_TEX_2D_ARRAY)
+        return dressi_fail(ctx, DRESSI_EINVAL, "texture_bwd: jitter (frame > 0) is for 2-D and cube textures");
     hipStream_t st = (hipStream_t)stream;
     int32_t *inv = nullptr;
-    float *part = nullptr;
+    float *part = nullptr, *jc = nullptr, *jg = nullptr;
+    const int cd = td->kind == DRESSI_TEX_CUBE ? 3 : 2;
     int64_t cells = (int64_t)tex_faces(*td) * td->Ht * td->Wt;
     if (grad_tex) {
         Carver c;
         size_t o_inv = c.take(sizeof(int32_t) * (size_t)cells * (S > 0 ? S : 1));
         size_t o_part = c.take(dressi_invuv_part_bytes(cells, td->Ct, S));
+        size_t o_jc = jit ? c.take(sizeof(float) * (size_t)n * cd) : 0;
+        size_t o_jg = jit ? c.take(sizeof(float) * (size_t)n * td->Ct) : 0;
         rc = dressi_scratch(ctx, c.off, st);
         if (rc) return rc;
         inv = at<int32_t>(ctx->scratch, o_inv);
         part = at<float>(ctx->scratch, o_part);
+        if (jit) {
+            jc = at<float>(ctx->scratch, o_jc);
+            jg = at<float>(ctx->scratch, o_jg);
+        }
     }
-    tex_bwd_pixels(tex, *td, coord, tri_id, npix, S, grad_out, grad_coord, inv, st, ctx->skip_empty);
-    if (grad_tex) tex_gather(*td, coord, tri_id, npix, S, inv, grad_out, part, grad_tex, st);
+    if (!jit) {
+        tex_bwd_pixels(tex, *td, coord, tri_id, npix, S, grad_out, grad_coord, inv, st, ctx->skip_empty);
+        if (grad_tex) tex_gather(*td, coord, tri_id, npix, S, inv, grad_out, part, grad_tex, st);
+        return dressi_launch_check(ctx, "texture_bwd");
+    }
+    // jittered registration beside the unmoved coordinate gradient
+    tex_bwd_pixels(tex, *td, coord, tri_id, npix, S, grad_out, grad_coord, nullptr, st, ctx->skip_empty);
+    if (S > 0) dressi_fill_i32(inv, -1, cells * S, st);
+    if (n > 0) {
+        const Jitter j = jitter_of_frame(frame);
+        const int g = (int)((n + 255) / 256);
+        switch (td->Ct) {
+        case 3: DR_LAUNCH("k_invuv_jitter", (k_invuv_jitter<3>), g, 256, 0, st, *td, coord, tri_id, H, W, S,
+                          grad_out, j, jc, jg, inv); break;
+        case 4: DR_LAUNCH("k_invuv_jitter", (k_invuv_jitter<4>), g, 256, 0, st, *td, coord, tri_id, H, W, S,
+                          grad_out, j, jc, jg, inv); break;
+        case 8: DR_LAUNCH("k_invuv_jitter", (k_invuv_jitter<8>), g, 256, 0, st, *td, coord, tri_id, H, W, S,
+                          grad_out, j, jc, jg, inv); break;
+        default: DR_LAUNCH("k_invuv_jitter", (k_invuv_jitter<0>), g, 256, 0, st, *td, coord, tri_id, H, W, S,
+                           grad_out, j, jc, jg, inv); break;
+        }
+    }
+    tex_gather(*td, jc, tri_id, npix, S, inv, jg, part, grad_tex, st);
     return dressi_launch_check(ctx, "texture_bwd");
 }
 

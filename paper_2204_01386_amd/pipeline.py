@@ -65,6 +65,9 @@ class _TwoStreams:
 
     concurrent = False
     _forked = False
+    # inverse-UV jitter of the texel gradients (dressi_texture_bwd's frame;
+    # 0 = none).  A captured graph keeps the frame it was recorded with.
+    frame = 0
     # every consumer in a step reads per-fragment buffers only at non-empty
     # slots, so the step's calls leave the entries of empty slots unwritten
     skip_empty = True
@@ -124,13 +127,15 @@ class _TwoStreams:
         H, W = self.H, self.W
         if not self._on("texel"):
             self._chk(_lib.dressi_texture_bwd(self.ctx.handle, _p(tex), C.byref(desc), _p(coord), _p(self.tri_id),
-                                              S, H, W, _p(grad_out), _p(grad_tex), _p(grad_coord), self._s()), what)
+                                              S, H, W, _p(grad_out), self.frame, _p(grad_tex), _p(grad_coord),
+                                              self._s()), what)
             return
         self._fork("texel")
         self._chk2(_lib.dressi_texture_bwd(self._h2("texel"), _p(tex), C.byref(desc), _p(coord), _p(self.tri_id), S,
-                                           H, W, _p(grad_out), _p(grad_tex), None, self._sa("texel")), what, "texel")
+                                           H, W, _p(grad_out), self.frame, _p(grad_tex), None, self._sa("texel")),
+                   what, "texel")
         self._chk(_lib.dressi_texture_bwd(self.ctx.handle, _p(tex), C.byref(desc), _p(coord), _p(self.tri_id), S,
-                                          H, W, _p(grad_out), None, _p(grad_coord), self._s()), what + " coord")
+                                          H, W, _p(grad_out), 0, None, _p(grad_coord), self._s()), what + " coord")
 
 
 class Step(_TwoStreams):
@@ -1086,11 +1091,11 @@ class PbsStep:
         ck(_lib.dressi_shade_pbs_bwd(h, C.byref(self._pin), _p(st.eye), _p(st.tri_id), B, K * H * W, _p(st.g_layer),
                                      None, None, C.byref(self._pg), s), "shade_pbs_bwd")
         ck(_lib.dressi_texture_bwd(h, _p(self.irr), C.byref(self.cube_irr), _p(self.dir_n), _p(st.tri_id), S, H, W,
-                                   _p(self.g_irr_s), _p(self.g_irr), None, s), "texture_bwd irradiance")
+                                   _p(self.g_irr_s), 0, _p(self.g_irr), None, s), "texture_bwd irradiance")
         for l in range(L):
             ck(_lib.dressi_texture_bwd(h, self._pref_level(self.pref, l), C.byref(self.cube_pref), _p(self.dir_r),
                                        self._pref_level(self.ltid, l), S, H, W, self._pref_level(self.g_pref_s, l),
-                                       self._pref_level(self.g_pref, l), None, s), "texture_bwd prefiltered")
+                                       0, self._pref_level(self.g_pref, l), None, s), "texture_bwd prefiltered")
         ck(_lib.dressi_ibl_filter_bwd(h, C.byref(self.desc), _p(self.norm), _p(self.g_irr), _p(self.g_pref),
                                       _p(self.g_env), s), "ibl_filter_bwd")
         ck(_lib.dressi_texture_grad_invuv(h, C.byref(st.desc), _p(st.uvbuf), _p(st.tri_id), S, H, W, _p(self.ts.inv),

@@ -384,6 +384,56 @@ def test_texture_config2_full(B):
     assert_grad_close(host(gt), gt_o, what="grad_tex cfg2")
 
 
+@pytest.mark.parametrize("frame", [1, 2, 3, 7, 1000, 123457])
+@pytest.mark.parametrize("kind,wrap", [(0, (0, 1)), (0, (1, 0)), (1, (1, 1))])
+def test_texture_bwd_jitter(B, frame, kind, wrap):
+    """The inverse UV with Sobol jitter (frame >= 1, §3.3.2) against the
+    oracle's jittered samples fed to its unjittered inverse UV: the texture
+    gradient at rel 1e-4 (a different winner would move whole texel sums);
+    the coordinate gradient does not depend on the frame."""
+    rng = np.random.default_rng(frame % 97 + 3 * kind)
+    S, H, W = 3, 41, 37
+    ys, xs = np.meshgrid(np.arange(H) + 0.5, np.arange(W) + 0.5, indexing="ij")
+    tid = np.where(rng.random((S, H, W)) < 0.9, rng.integers(0, 7, (S, H, W)), -1).astype(np.int32)
+    tid[:, :, :3] = -1
+    if kind == 0:
+        tex = rng.random((29, 23, 4)).astype(np.float32)
+        base = np.stack([0.02 * xs + 0.003 * ys, 0.025 * ys - 0.004 * xs], -1)
+        coord = (base[None] + 0.01 * rng.standard_normal((S, H, W, 2)) - 0.1).astype(np.float32)
+    else:
+        tex = rng.random((6, 9, 9, 3)).astype(np.float32)
+        ang = 0.08 * xs, 0.07 * ys
+        base = np.stack([np.cos(ang[0]) * np.cos(ang[1]), np.sin(ang[1]), np.sin(ang[0]) * np.cos(ang[1])], -1)
+        coord = (base[None] + 0.02 * rng.standard_normal((S, H, W, 3))).astype(np.float32)
+    g = rng.standard_normal((S, H, W, tex.shape[-1])).astype(np.float32)
+    kw = dict(kind=kind, wrap_u=wrap[0], wrap_v=wrap[1]) if kind == 0 else dict(kind=oracle.TEX_CUBE)
+    jc, jt, jg = oracle.jitter_samples(coord, tid, g.astype(np.float64), frame)
+    assert (jt >= 0).sum() > 0.5 * (tid >= 0).sum()
+    gt_o = oracle.texture_bwd_tex(tex.shape, jc, jt, jg, **kw)
+    gc_o = oracle.texture_bwd_coord(tex, coord, g, tid, **kw)
+    gt, gc = B.dressi_texture_bwd(dev(tex), dev(coord), dev(tid), dev(g), kind, wrap[0], wrap[1], frame=frame)
+    assert_grad_close(host(gt), gt_o, what=f"jittered grad_tex frame {frame}")
+    assert_grad_close(host(gc), gc_o, what="grad_coord")
+    # the frame moves the winners: not the unjittered gradient
+    gt0, _ = B.dressi_texture_bwd(dev(tex), dev(coord), dev(tid), dev(g), kind, wrap[0], wrap[1], frame=0)
+    assert not np.array_equal(host(gt0), host(gt))
+
+
+def test_texture_bwd_jitter_config2_full(B):
+    """Frame 5 at config-2 sizes: the oracle's raster of the 81,920-triangle
+    mesh at 512^2 on the 1024^2 RGBA texture."""
+    s = scenes.config2()
+    pc = to_clip(s.pos, s.mvp)
+    tid_o, _, bary_o, _ = oracle.rasterize(pc, s.tris, 512, 512, K=1)
+    uv = oracle.interpolate_f32(s.uv, s.uv_tris, tid_o, bary_o.astype(np.float32)).reshape(1, 512, 512, 2)
+    t = tid_o.reshape(1, 512, 512)
+    g = np.random.default_rng(4).standard_normal((1, 512, 512, 4)).astype(np.float32)
+    jc, jt, jg = oracle.jitter_samples(uv, t, g.astype(np.float64), 5)
+    gt_o = oracle.texture_bwd_tex(s.tex.shape, jc, jt, jg)
+    gt, _ = B.dressi_texture_bwd(dev(s.tex), dev(uv), dev(t), dev(g), need_coord=False, frame=5)
+    assert_grad_close(host(gt), gt_o, what="jittered grad_tex cfg2")
+
+
 # ---------------------------------------------------------------------------
 # softras
 # ---------------------------------------------------------------------------
