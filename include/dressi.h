@@ -89,10 +89,33 @@ int dressi_reserve(dressi_ctx *ctx, size_t bytes, int64_t bin_entries);
  * graph capture).  Pass the largest shapes of the step. */
 size_t dressi_scratch_bytes(int B, int V, int T, int H, int W, int K, float r,
                             int Va, int C, int64_t tex_cells, int tex_slices);
-/* (The entry points declared after the rendering stages, the inverse-UV
- * split, the optimisation loop and image-based PBS, are not covered by this
- * estimate: one eager call of each with the step's shapes sizes the scratch
- * before a capture, or a capture without it fails with DRESSI_ENOMEM.) */
+/* (dressi_scratch_bytes covers the four rendering stages; the limits below
+ * cover every entry point.) */
+
+/* The largest shapes a context will be called with, for sizing its scratch
+ * once, before any graph capture.  Zero fields are unused stages. */
+typedef struct {
+    int B, V, T, H, W, K; /* views (or 1 for an uneven batch), vertices, triangles,
+                             image, layers of rasterize(_banded, _batched)(_bwd),
+                             fragment_index, adjacency and vertex_attrs(_bwd)   */
+    float r;              /* soft reach (0 = hard only)                           */
+    int Va, C;            /* attribute rows and channels of interpolate_bwd        */
+    int64_t tex_cells;    /* faces (or layers) x Ht x Wt of the largest texture    */
+    int tex_channels;     /* its channels Ct                                       */
+    int tex_slices;       /* slices S of a texture_bwd call                        */
+    int jitter;           /* 1 if texture_bwd is called with frame >= 1            */
+    int ibl_S, ibl_Si, ibl_Sp, ibl_L; /* ibl_filter(_bwd) shapes (0 = none)        */
+    int64_t pbs_fragments; /* N of shade_pbs_bwd with a material gradient          */
+    int64_t bin_entries;  /* tile-bin capacity (0 = automatic for the shapes)      */
+} dressi_limits;
+/* Bytes of scratch that every entry point needs at these limits (the
+ * largest single call, with every optional index built internally). */
+size_t dressi_limits_scratch_bytes(const dressi_limits *l);
+/* Grows the context's scratch arena, its zeroed counters and the tile-bin
+ * capacity to the limits: afterwards no call within them allocates, so a
+ * graph can be captured without an eager call first.  Synchronises the
+ * device. */
+int dressi_reserve_limits(dressi_ctx *ctx, const dressi_limits *l);
 /* Waits for `stream`, then returns DRESSI_EOVERFLOW (and clears the flag) if a
  * rasterization since the last check overflowed the bin capacity; *needed
  * receives the capacity that call required (may be NULL). */

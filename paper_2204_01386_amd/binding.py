@@ -142,6 +142,21 @@ EXPORTED = sorted(list(_SIG) + ["dressi_last_error", "dressi_scratch_bytes", "dr
                                 "dressi_profile_read"])
 
 
+class Limits(C.Structure):
+    """dressi_limits: the largest shapes a context will be called with."""
+    _fields_ = [("B", _i), ("V", _i), ("T", _i), ("H", _i), ("W", _i), ("K", _i), ("r", _f), ("Va", _i),
+                ("C", _i), ("tex_cells", _i64), ("tex_channels", _i), ("tex_slices", _i), ("jitter", _i),
+                ("ibl_S", _i), ("ibl_Si", _i), ("ibl_Sp", _i), ("ibl_L", _i), ("pbs_fragments", _i64),
+                ("bin_entries", _i64)]
+
+
+_lib.dressi_limits_scratch_bytes.argtypes = [C.POINTER(Limits)]
+_lib.dressi_limits_scratch_bytes.restype = C.c_size_t
+_lib.dressi_reserve_limits.argtypes = [_vp, C.POINTER(Limits)]
+_lib.dressi_reserve_limits.restype = C.c_int
+EXPORTED = sorted(EXPORTED + ["dressi_limits_scratch_bytes", "dressi_reserve_limits"])
+
+
 class DressiError(RuntimeError):
     pass
 
@@ -164,6 +179,9 @@ class Context:
 
     def reserve(self, nbytes: int = 0, bin_entries: int = 0):
         self.check(_lib.dressi_reserve(self.handle, nbytes, bin_entries), "dressi_reserve")
+
+    def reserve_limits(self, limits: "Limits"):
+        self.check(_lib.dressi_reserve_limits(self.handle, C.byref(limits)), "dressi_reserve_limits")
 
     def tune(self, key: int, value: int):
         self.check(_lib.dressi_tune(self.handle, key, value), "dressi_tune")

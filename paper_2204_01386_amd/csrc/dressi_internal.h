@@ -48,6 +48,15 @@ int dressi_launch_check(dressi_ctx *ctx, const char *what);
 // (L-infinity dilation of radius rho >= 0), one byte per pixel [B,H,W].
 void dressi_edge_mask(const int32_t *tri_id, const float *dist, int B, int K, int H, int W, int rho,
                       uint8_t *bnd, uint8_t *rows, uint8_t *edge, hipStream_t st);
+// Scratch each file's entry points need at the given limits (the largest
+// call, with every optional index built internally); for dressi_limits.
+size_t dr_need_raster(const dressi_limits &l, int64_t cap);   // raster.hip
+size_t dr_need_interp(const dressi_limits &l);                // interp.hip
+size_t dr_need_texture(const dressi_limits &l);               // texture.hip
+size_t dr_need_shade(const dressi_limits &l);                 // shade.hip
+size_t dr_need_optim(const dressi_limits &l);                 // optim.hip
+size_t dr_need_pbs(const dressi_limits &l);                   // pbs.hip
+int64_t dr_tile_capacity(const dressi_limits &l);             // raster.hip
 // Looks up, once per device, the device address of the fixed scratch of
 // dressi_softras_noalloc (softras.hip); `device` must be current.
 int dressi_softras_noalloc_setup(int device);

@@ -478,3 +478,17 @@ extern "C" int dressi_interpolate_bwd(dressi_ctx *ctx, const float *attr, int Ba
     }
     return dressi_launch_check(ctx, "interpolate_bwd");
 }
+
+// interpolate_bwd with grad_attr, the fragment index and adjacency built
+// internally (the largest of its calls)
+size_t dr_need_interp(const dressi_limits &l) {
+    const int B = l.B, K = std::max(l.K, 1), H = l.H, W = l.W, T = l.T, Va = l.Va, C = l.C;
+    if (B <= 0 || H <= 0 || W <= 0 || Va <= 0 || C <= 0) return 0;
+    const int nt = tiles_x(W) * tiles_y(H);
+    Carver c;
+    c.take(dressi_fragindex_bytes(B, K, H, W, T));
+    c.take(adjacency_buf_bytes(Va, T));
+    c.take(std::max(dressi_fragindex_tmp_bytes(B, K, H, W, T), dressi_adjacency_tmp_bytes(Va, T)));
+    c.take(sizeof(float) * (size_t)B * nt * DRESSI_TILE_PIX * K * 3 * C);
+    return c.off;
+}

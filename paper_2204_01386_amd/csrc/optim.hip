@@ -235,3 +235,14 @@ extern "C" int dressi_laplacian_reg(dressi_ctx *ctx, const float *pos, const int
     if (value) DR_LAUNCH("k_lap_value", (k_lap_value), 1, LAP_BS, 0, st, part, nb, V, lam0, gamma, s, value);
     return dressi_launch_check(ctx, "laplacian_reg");
 }
+
+// laplacian_reg with the adjacency built internally
+size_t dr_need_optim(const dressi_limits &l) {
+    const int V = std::max(l.V, 0), T = std::max(l.T, 0);
+    Carver c;
+    c.take(adjacency_buf_bytes(V, T));
+    c.take(dressi_adjacency_tmp_bytes(V, T));
+    c.take(sizeof(float4) * (size_t)V);
+    c.take(sizeof(double) * (size_t)((V + LAP_BS - 1) / LAP_BS));
+    return c.off;
+}

@@ -610,3 +610,20 @@ extern "C" int dressi_shade_pbs_bwd(dressi_ctx *ctx, const dressi_pbs_in *in, co
         DR_LAUNCH("k_pbs_material_sum", (k_pbs_material_sum), 1, PBS_BS, 0, st, part, nb, grad->material);
     return dressi_launch_check(ctx, "shade_pbs_bwd");
 }
+
+// ibl_filter(_bwd) tables and shade_pbs_bwd's material partials
+size_t dr_need_pbs(const dressi_limits &l) {
+    size_t need = 0;
+    if (l.ibl_S > 0) {
+        const int64_t ne = 6ll * l.ibl_S * l.ibl_S;
+        const int64_t no = 6ll * l.ibl_Si * l.ibl_Si + (int64_t)l.ibl_L * 6 * l.ibl_Sp * l.ibl_Sp;
+        Carver c;
+        c.take(sizeof(double4) * (size_t)ne);
+        c.take(sizeof(double4) * (size_t)no);
+        c.take(sizeof(float4) * (size_t)no);
+        need = c.off;
+    }
+    if (l.pbs_fragments > 0)
+        need = std::max(need, sizeof(double) * 2 * (size_t)((l.pbs_fragments + PBS_BS - 1) / PBS_BS));
+    return need;
+}

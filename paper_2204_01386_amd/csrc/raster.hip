@@ -1553,6 +1553,60 @@ extern "C" int dressi_rasterize_batched_bwd(dressi_ctx *ctx, const float *pos_cl
 // ---------------------------------------------------------------------------
 // worst-case scratch of one call of each kind, for dressi_reserve
 // ---------------------------------------------------------------------------
+int64_t dr_tile_capacity(const dressi_limits &l) {
+    const int nt = tiles_x(l.W) * tiles_y(l.H);
+    const int64_t cap = default_tile_capacity(l.B, l.T, nt, soft_margin(l.r, l.W));
+    return std::min<int64_t>(std::max<int64_t>(cap, l.bin_entries), 1 << 26);
+}
+
+// rasterize (full, banded or batched), rasterize_bwd and fragment_index
+size_t dr_need_raster(const dressi_limits &l, int64_t cap) {
+    const int B = l.B, T = l.T, H = l.H, W = l.W, K = std::max(l.K, 1);
+    if (B <= 0 || H <= 0 || W <= 0) return 0;
+    const int nt = tiles_x(W) * tiles_y(H);
+    size_t need = 0;
+    {
+        Carver c;
+        size_t o[2];
+        raster_scratch(B, T, nt, (int)cap, c, o);
+        if (l.r > 0.0f) c.take(3 * (size_t)B * H * W);
+        need = std::max(need, c.off);
+    }
+    {
+        Carver c;
+        c.take(dressi_fragindex_bytes(B, K, H, W, T));
+        c.take(adjacency_buf_bytes(l.V, T));
+        c.take(std::max(dressi_fragindex_tmp_bytes(B, K, H, W, T), dressi_adjacency_tmp_bytes(l.V, T)));
+        c.take(sizeof(float) * partial_floats(B, K, H, W, 9));
+        need = std::max(need, c.off);
+    }
+    return std::max(need, dressi_fragindex_tmp_bytes(B, K, H, W, T));
+}
+
+extern "C" size_t dressi_limits_scratch_bytes(const dressi_limits *l) {
+    if (!l || l->B < 0 || l->V < 0 || l->T < 0 || l->H < 0 || l->W < 0 || l->K < 0) return 0;
+    size_t need = dr_need_raster(*l, dr_tile_capacity(*l));
+    need = std::max(need, dr_need_interp(*l));
+    need = std::max(need, dr_need_texture(*l));
+    need = std::max(need, dr_need_shade(*l));
+    need = std::max(need, dr_need_optim(*l));
+    need = std::max(need, dr_need_pbs(*l));
+    need = std::max(need, 2 * (size_t)std::max(l->B, 0) * std::max(l->H, 0) * std::max(l->W, 0));  // softras
+    return need;
+}
+
+extern "C" int dressi_reserve_limits(dressi_ctx *ctx, const dressi_limits *l) {
+    if (!ctx) return DRESSI_EINVAL;
+    if (!l) return dressi_fail(ctx, DRESSI_EINVAL, "reserve_limits: null limits");
+    const size_t bytes = dressi_limits_scratch_bytes(l);
+    const int64_t cap = dr_tile_capacity(*l);
+    int rc = dressi_reserve(ctx, bytes, cap);
+    if (rc) return rc;
+    const size_t nt = (size_t)tiles_x(l->W) * tiles_y(l->H);
+    const size_t nc = std::max((size_t)std::max(l->B, 1) * nt, (size_t)std::max(l->B, 1) * std::max(l->T, 0));
+    return dressi_counters(ctx, nc, nullptr);
+}
+
 extern "C" size_t dressi_scratch_bytes(int B, int V, int T, int H, int W, int K, float r, int Va,
                                        int C, int64_t tex_cells, int tex_slices) {
     if (B < 0 || V < 0 || T < 0 || H < 0 || W < 0 || K < 1) return 0;

@@ -709,3 +709,13 @@ extern "C" int dressi_loss_l2(dressi_ctx *ctx, const float *color, const float *
     DR_LAUNCH("k_loss_sum", (k_loss_sum), 1, LOSS_BS, 0, st, partial, (int)nb, weight ? 1.0f : inv, loss);
     return dressi_launch_check(ctx, "loss_l2");
 }
+
+// vertex_attrs(_bwd) with the adjacency built internally, and the loss's
+// block partials
+size_t dr_need_shade(const dressi_limits &l) {
+    Carver c;
+    c.take(adjacency_buf_bytes(std::max(l.V, 0), std::max(l.T, 0)));
+    c.take(dressi_adjacency_tmp_bytes(std::max(l.V, 0), std::max(l.T, 0)));
+    c.take(sizeof(float) * 3 * (size_t)std::max(l.V, 0));
+    return std::max(c.off, sizeof(float) * (size_t)LOSS_MAX_BLOCKS);
+}

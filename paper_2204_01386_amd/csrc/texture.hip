@@ -748,3 +748,18 @@ extern "C" int dressi_texture_grad_invuv(dressi_ctx *ctx, const dressi_tex_desc 
     tex_gather(*td, coord, tri_id, (int64_t)H * W, S, inv, grad_out, part, grad_tex, st);
     return dressi_launch_check(ctx, "texture_grad_invuv");
 }
+
+// texture_bwd (with jitter when asked) and texture_grad_invuv
+size_t dr_need_texture(const dressi_limits &l) {
+    if (l.tex_cells <= 0 || l.tex_channels <= 0) return 0;
+    const int S = std::max(l.tex_slices, 1);
+    Carver c;
+    c.take(sizeof(int32_t) * (size_t)l.tex_cells * S);
+    c.take(dressi_invuv_part_bytes(l.tex_cells, l.tex_channels, S));
+    if (l.jitter) {
+        const size_t n = (size_t)S * std::max(l.H, 0) * std::max(l.W, 0);
+        c.take(sizeof(float) * n * 3);
+        c.take(sizeof(float) * n * l.tex_channels);
+    }
+    return c.off;
+}

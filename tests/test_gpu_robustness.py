@@ -177,3 +177,84 @@ def test_smallest_repeat_texture_gradient_is_the_exact_adjoint(B):
     tex2 = rng.random((3, 2, 4)).astype(np.float32)
     with pytest.raises(B.DressiError, match="EINVAL"):
         B.dressi_texture_bwd(dev(tex2), dev(uv), dev(tid), dev(g), wrap_u=B.WRAP_REPEAT, wrap_v=B.WRAP_CLAMP)
+
+
+def test_reserve_limits_then_capture_without_eager_calls(B):
+    """A fresh context sized once by dressi_reserve_limits runs the stages
+    inside a graph capture with no eager call first (a call that had to grow
+    its scratch or counters would fail there with ENOMEM); the replays equal
+    an eager run of the same calls on a context that grew as it went."""
+    import ctypes as C
+    from paper_2204_01386_amd.binding import _lib, _ptr, _stream, Limits, TexDesc
+    s = scenes.config3(n_views=2, subdiv=3, H=96, tex_size=128, env_size=16)
+    Bv, H, W, K, r = 2, 96, 96, 3, 0.05
+    pc = dev(oracle.transform_f32(s.pos, s.mvp))
+    pos, tris = dev(s.pos), dev(s.tris)
+    V, T = s.pos.shape[0], s.tris.shape[0]
+    rng = np.random.default_rng(8)
+    attr = dev(rng.standard_normal((V, 9)).astype(np.float32))
+    tex = dev(np.ascontiguousarray(s.tex))
+    Ht, Wt, Ct = s.tex.shape
+    e = lambda *sh, dt=torch.float32: torch.zeros(sh, dtype=dt, device="cuda")
+    gi = dev(rng.standard_normal((Bv, K, H, W, 9)).astype(np.float32))
+    gu = dev(rng.standard_normal((Bv, K, H, W, Ct)).astype(np.float32))
+    uvp = dev(rng.random((Bv, K, H, W, 2)).astype(np.float32))
+    gdist = dev(rng.standard_normal((Bv, K, H, W)).astype(np.float32))
+    tgt = dev(rng.random((Bv, H, W, 4)).astype(np.float32))
+    td = TexDesc(B.TEX_2D, Ht, Wt, Ct, B.WRAP_REPEAT, B.WRAP_CLAMP)
+
+    def buffers():
+        return dict(tid=e(Bv, K, H, W, dt=torch.int32), bary=e(Bv, K, H, W, 2), dist=e(Bv, K, H, W),
+                    out=e(Bv, K, H, W, 9), gattr=e(V, 9), gbary=e(Bv, K, H, W, 2), gclip=e(Bv, V, 4),
+                    gtex=e(Ht, Wt, Ct), gcoord=e(Bv, K, H, W, 2), col=e(Bv, H, W, 3), sil=e(Bv, H, W),
+                    E=e(Bv, H, W, dt=torch.uint8), glc=e(Bv, K, H, W, 3), gd=e(Bv, K, H, W), loss=e(1),
+                    gc=e(Bv, H, W, 3), gs=e(Bv, H, W), gpos=e(V, 3), lap=e(V, 3), lapv=e(1))
+
+    def run(ctx, o):
+        h, st = ctx.handle, _stream()
+        ck = ctx.check
+        ck(_lib.dressi_rasterize_banded(h, _ptr(pc), _ptr(tris), Bv, V, T, H, W, K, r, 0, r, B.BLEND_HSR,
+                                        _ptr(o["tid"]), _ptr(o["bary"]), _ptr(o["dist"]), st), "raster")
+        ck(_lib.dressi_interpolate(h, _ptr(attr), 1, V, 9, _ptr(tris), T, _ptr(o["tid"]), _ptr(o["bary"]), Bv, K,
+                                   H, W, _ptr(o["out"]), st), "interp")
+        ck(_lib.dressi_interpolate_bwd(h, _ptr(attr), 1, V, 9, _ptr(tris), T, _ptr(o["tid"]), _ptr(o["bary"]), Bv,
+                                       K, H, W, _ptr(gi), None, None, None, _ptr(o["gattr"]), _ptr(o["gbary"]),
+                                       st), "interp_bwd")
+        ck(_lib.dressi_rasterize_bwd(h, _ptr(pc), _ptr(tris), Bv, V, T, H, W, K, r, 0, _ptr(o["tid"]),
+                                     _ptr(o["gbary"]), _ptr(gdist), None, None, _ptr(o["gclip"]), st), "rbwd")
+        ck(_lib.dressi_texture_bwd(h, _ptr(tex), C.byref(td), _ptr(uvp), _ptr(o["tid"]), Bv * K, H, W, _ptr(gu), 3,
+                                   _ptr(o["gtex"]), _ptr(o["gcoord"]), st), "tex_bwd")
+        ck(_lib.dressi_softras(h, _ptr(o["out"]), _ptr(o["dist"]), _ptr(o["tid"]), Bv, K, H, W, 3, r / 7, r,
+                               B.BLEND_HSR, _ptr(o["col"]), _ptr(o["sil"]), _ptr(o["E"]), st), "softras")
+        ck(_lib.dressi_loss_l2(h, _ptr(o["col"]), _ptr(o["sil"]), _ptr(tgt), None, Bv, H, W, _ptr(o["loss"]),
+                               _ptr(o["gc"]), _ptr(o["gs"]), st), "loss")
+        ck(_lib.dressi_softras_bwd(h, _ptr(o["out"]), _ptr(o["dist"]), _ptr(o["tid"]), Bv, K, H, W, 3, r / 7,
+                                   _ptr(o["E"]), _ptr(o["gc"]), _ptr(o["gs"]), _ptr(o["glc"]), _ptr(o["gd"]), st),
+           "softras_bwd")
+        ck(_lib.dressi_vertex_attrs_bwd(h, _ptr(pos), _ptr(tris), V, T, 9, None, _ptr(o["gattr"]), None,
+                                        _ptr(o["gpos"]), st), "vattr_bwd")
+        ck(_lib.dressi_laplacian_reg(h, _ptr(pos), _ptr(tris), V, T, None, 1.0, 0.99, None, None, _ptr(o["lap"]),
+                                     _ptr(o["lapv"]), st), "laplacian")
+
+    lim = Limits(B=Bv, V=V, T=T, H=H, W=W, K=K, r=r, Va=V, C=9, tex_cells=Ht * Wt, tex_channels=Ct,
+                 tex_slices=Bv * K, jitter=1)
+    assert B._lib.dressi_limits_scratch_bytes(C.byref(lim)) > 0
+    ca = B.Context(torch.cuda.current_device())
+    ca.reserve_limits(lim)
+    oa = buffers()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        run(ca, oa)                      # the first calls on this context are captured ones
+    cb = B.Context(torch.cuda.current_device())
+    ob = buffers()
+    run(cb, ob)
+    torch.cuda.synchronize()
+    for rep in range(2):
+        for v in oa.values():
+            v.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        for k in ob:
+            assert np.array_equal(host(oa[k]), host(ob[k])), f"replay {rep}: {k} differs from the eager run"
+    assert (host(ob["tid"]) >= 0).any() and np.abs(host(ob["gtex"])).max() > 0
