@@ -322,7 +322,7 @@ int dressi_texture_bwd(dressi_ctx *ctx, const float *tex, const dressi_tex_desc 
 
 /* The two halves of the texture gradient of dressi_texture_bwd, for a scene
  * whose geometry is held fixed while only textures are optimised (the
- * paper's reactive cache, §3.2.3, skips the unchanged rasterization; its
+ * paper's reactive cache, §3.3.3, skips the unchanged rasterization; its
  * cross-platform table times texture-only iterations): the inverse-UV map
  * depends only on coord and tri_id, so it is built once and every later
  * step only gathers.

@@ -119,7 +119,7 @@ def run_fit(scene: Scene, n_sil: int = 300, n_tex: int = 200, every: int = 25, l
 
 def kr_sweep(Ks=(1, 2, 3, 4, 5), r_px=(1, 2, 3, 5, 7), checkpoints=(500, 2500), seed: int = 0,
              blend: str = "hsr", lap_gamma: float = 0.999) -> dict:
-    """The paper's validation of HardSoftRas settings (§4.2: a heatmap over K
+    """The paper's validation of HardSoftRas settings (§4.3: a heatmap over K
     and r of the fitted geometry's distance to the target, early and late in
     the optimisation) on the sphere-to-pear silhouette fit: for every (K, r)
     the target is rendered with the same setting, and the mean distance of

@@ -452,7 +452,7 @@ class Step(_TwoStreams):
 class TextureStep:
     """Texture-only optimisation of a scene whose geometry is held fixed.
 
-    The paper's reactive cache (§3.2.3) skips graph nodes whose inputs did
+    The paper's reactive cache (§3.3.3) skips graph nodes whose inputs did
     not change since they were last computed; for texture optimisation that
     removes the whole rasterization (its cross-platform table times
     texture-only and geometry iterations separately).  Here the cached nodes
