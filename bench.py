@@ -49,13 +49,15 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 5])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=8.0)
     ap.add_argument("--profile-steps", type=int, default=20)
     ap.add_argument("--only-graph", action="store_true",
                     help="only the captured-step replays (for external profilers)")
     ap.add_argument("--no-multiview", dest="multiview", action="store_false",
                     help="skip the 16-view batched-vs-plain measurement")
     ap.add_argument("--multiview-steps", type=int, default=30)
+    ap.add_argument("--no-large", dest="large", action="store_false",
+                    help="skip the large configuration (8 views 2048^2, 1 M triangles)")
     ap.add_argument("--no-uneven", dest="uneven", action="store_false",
                     help="skip the 64-instance uneven batch measurement")
     ap.add_argument("--uneven-steps", type=int, default=20)
@@ -114,12 +116,16 @@ def scene_for(cfg):
 
 # ---------------------------------------------------------------------------
 # Algorithmic bytes.  A tensor that crosses the library boundary (a stage's
-# input or output) is read once and written once at its dtype; a texture read
-# counts only the texels that can be touched, min(Ht*Wt, 4 * covered
-# fragments); each inverse-UV slice is cleared and read once in full and
-# written once per covered fragment.  Internal scratch (setup records, bins,
-# fragment index, per-tile partial sums) is not counted, so implementation
-# overhead shows up as a lower fraction of the roofline.
+# input or output) is read once and written once at its dtype, where the
+# method needs it: every per-fragment stage reads tri_id at each of the
+# N = B*K*H*W fragment slots (it decides which slots are empty) and reads and
+# writes the other per-fragment planes only at the covered fragments; the
+# rasterizer writes every slot.  A texture read counts only the texels that
+# can be touched, min(Ht*Wt, 4 * covered fragments); each inverse-UV slice is
+# cleared and read once in full and written once per covered fragment.
+# Internal scratch (setup records, bins, fragment index, per-tile partial
+# sums) is not counted, so implementation overhead shows up as a lower
+# fraction of the roofline.
 # ---------------------------------------------------------------------------
 # HBM traffic per launch from two rocprofv3 counter runs of this script on the
 # headline workload (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch).  Each
@@ -171,95 +177,99 @@ class Shapes:
         return min(cells, 4 * self.cov) * C * 4
 
 
+def _shade_in(z: Shapes):
+    """Per-fragment shading inputs (bytes per covered fragment): normal,
+    position (Phong), albedo (sampled) or colour (Lambert), tangent and
+    normal-map sample and environment sample (with the environment map)."""
+    b = 12 + (0 if z.mode == 0 else 12) + (z.Ct * 4 if z.Ct else 12)
+    return b + (12 + 12 if z.env else 0)
+
+
 def call_bytes(z: Shapes):
     """Algorithmic bytes of every library call of one step, by call."""
-    N, P, V, T, Cv, B = z.N, z.P, z.V, z.T, z.Cv, z.B
+    N, P, V, T, Cv, B, c = z.N, z.P, z.V, z.T, z.Cv, z.B, z.cov
     d = 4 if z.soft else 0
-    sh_in = N * 4 + N * 6 * 4 + (N * z.Ct * 4 if z.Ct else N * 12) + (N * 12 if z.env else 0) + B * 12
+    sh_in = N * 4 + c * _shade_in(z) + B * 12
+    g_geo = 12 + (0 if z.mode == 0 else 12) + (12 if z.env else 0)      # normal, pos, tangent gradients
     out = {
         "vertex_attrs": V * 12 + T * 12 + z.adj + (V * 12 if z.ex else 0) + V * Cv * 4,
         "transform": V * 12 + B * 64 + B * V * 16,
         "rasterize": B * V * 16 + T * 12 + N * (4 + 8 + d),
-        "interpolate": V * Cv * 4 + T * 12 + N * 12 + N * Cv * 4,
-        "softras": N * (12 + 4 + d) + P * (12 + 4 + 1),
+        "interpolate": V * Cv * 4 + T * 12 + N * 4 + c * 8 + c * Cv * 4,
+        "softras": N * 4 + c * (12 + d) + P * (12 + 4 + 1),
         "loss_l2": P * (12 + 4 + 16) + P * 16,
-        "softras_bwd": N * (12 + 4 + d) + P * (1 + 12 + 4) + N * (12 + d),
-        "shade": sh_in + N * 12,
-        "shade_bwd": sh_in + N * 12 + N * 6 * 4 + (N * z.Ct * 4 if z.Ct else N * 12),
-        "interpolate_bwd": N * 12 + N * Cv * 4 + V * Cv * 4 + T * 12 + z.adj + N * 8 + V * Cv * 4,
-        "rasterize_bwd": B * V * 16 + T * 12 + z.adj + N * (4 + 8 + d) + B * V * 16,
+        "softras_bwd": N * 4 + c * (12 + d) + P * (1 + 12 + 4) + c * (12 + d),
+        "shade": sh_in + c * 12,
+        "shade_bwd": sh_in + c * 12 + c * (g_geo + (z.Ct * 4 if z.Ct else 12)),
+        "interpolate_bwd": N * 4 + c * (8 + Cv * 4) + V * Cv * 4 + T * 12 + z.adj + (c * 8 if z.Ct else 0)
+                           + V * Cv * 4 + c * 8,
+        "rasterize_bwd": B * V * 16 + T * 12 + z.adj + N * 4 + c * (8 + d) + B * V * 16,
         "transform_bwd": B * V * 16 + B * 64 + V * 12,
         "vertex_attrs_bwd": V * 12 + T * 12 + z.adj + V * Cv * 4 + V * 12 + V * 12,
     }
     if z.Ct:
-        out["interpolate uv"] = z.Vuv * 8 + T * 12 + N * 12 + N * 8
-        out["texture"] = N * 12 + z.touched(z.cells, z.Ct) + N * z.Ct * 4
-        out["interpolate_bwd uv"] = z.Vuv * 8 + T * 12 + N * 12 + N * 8 + N * 8 + N * 8
-        out["texture_bwd"] = (N * 12 + z.touched(z.cells, z.Ct) + N * z.Ct * 4 + N * 8
-                              + z.S * z.cells * 4 * 2 + z.cov * 4
-                              + min(z.cov, z.S * z.cells) * (8 + z.Ct * 4) + z.cells * z.Ct * 4)
+        win = min(c, z.S * z.cells)
+        out["interpolate uv"] = z.Vuv * 8 + T * 12 + N * 4 + c * 8 + c * 8
+        out["texture"] = N * 4 + c * 8 + z.touched(z.cells, z.Ct) + c * z.Ct * 4
+        out["interpolate_bwd uv"] = z.Vuv * 8 + T * 12 + N * 4 + c * (8 + 8) + c * 8
+        out["texture_bwd"] = (N * 4 + c * (8 + z.Ct * 4) + z.touched(z.cells, z.Ct) + c * 8
+                              + z.S * z.cells * 4 * 2 + c * 4 + win * (8 + z.Ct * 4) + z.cells * z.Ct * 4)
     if z.env:
-        out["shade dir"] = N * 4 + N * 12 * 3 + B * 12 + N * 12
-        out["texture env"] = N * 16 + z.touched(z.ecells, 3) + N * 12
-        out["shade_bwd env"] = sh_in + N * 12 + N * 12
-        out["texture_bwd env"] = (N * 16 + z.touched(z.ecells, 3) + N * 12 + N * 12
-                                  + z.S * z.ecells * 4 * 2 + z.cov * 4
-                                  + min(z.cov, z.S * z.ecells) * (12 + 12) + z.ecells * 12)
+        ewin = min(c, z.S * z.ecells)
+        out["shade dir"] = N * 4 + c * (12 + 12 + 12 + 12) + B * 12 + c * 12
+        out["texture env"] = N * 4 + c * 12 + z.touched(z.ecells, 3) + c * 12
+        out["shade_bwd env"] = sh_in + c * 12 + c * 12
+        out["texture_bwd env"] = (N * 4 + c * (12 + 12) + z.touched(z.ecells, 3) + c * 12
+                                  + z.S * z.ecells * 4 * 2 + c * 4 + ewin * (12 + 12) + z.ecells * 12)
     return out
 
 
 def kernel_bytes(name, z: Shapes):
     """Algorithmic bytes per launch of a kernel (same accounting as above),
     or None for kernels that only move internal scratch."""
-    N, P, V, T, Cv, B = z.N, z.P, z.V, z.T, z.Cv, z.B
+    N, P, V, T, Cv, B, c = z.N, z.P, z.V, z.T, z.Cv, z.B, z.cov
     d = 4 if z.soft else 0
-    if name == "k_raster":
-        return N * (4 + 8 + d)
+    cb = call_bytes(z)
+    if name in ("k_raster", "k_raster_list"):
+        return cb["rasterize"] - B * V * 16 - T * 12
     if name == "k_setup_bin":
         return B * V * 16 + T * 12
     if name == "k_interp":        # per-vertex attributes and (textured) UVs: mean per launch
-        a = V * Cv * 4 + T * 12 + N * 12 + N * Cv * 4
-        if not z.Ct:
-            return a
-        return (a + z.Vuv * 8 + T * 12 + N * 12 + N * 8) // 2
+        return cb["interpolate"] if not z.Ct else (cb["interpolate"] + cb["interpolate uv"]) // 2
     if name == "k_tex_fwd":       # albedo (and environment) lookups: mean per launch
-        a = N * 12 + z.touched(z.cells, z.Ct) + N * z.Ct * 4
-        if not z.env:
-            return a
-        return (a + N * 16 + z.touched(z.ecells, 3) + N * 12) // 2
+        return cb["texture"] if not z.env else (cb["texture"] + cb["texture env"]) // 2
     if name == "k_invuv_gather" and not z.env:
-        return z.S * z.cells * 4 + min(z.cov, z.S * z.cells) * (8 + z.Ct * 4) + z.cells * z.Ct * 4
+        return z.S * z.cells * 4 + min(c, z.S * z.cells) * (8 + z.Ct * 4) + z.cells * z.Ct * 4
     if name == "k_tex_bwd_pixel" and not z.env:
-        return N * 12 + z.touched(z.cells, z.Ct) + N * z.Ct * 4 + N * 8 + z.cov * 4
+        return N * 4 + c * (8 + z.Ct * 4) + z.touched(z.cells, z.Ct) + c * 8 + c * 4
     if name == "k_blend":
-        return N * (12 + 4 + d) + P * (12 + 4 + 1)
+        return cb["softras"]
     if name == "k_blend_bwd":
-        return N * (12 + 4 + d) + P * (1 + 12 + 4) + N * (12 + d)
+        return cb["softras_bwd"]
     if name == "k_loss_l2":
-        return P * (12 + 4 + 16) + P * 16
+        return cb["loss_l2"]
     if name == "k_interp_bwd_tile":
-        return N * 12 + N * Cv * 4 + V * Cv * 4 + T * 12 + (N * 8 if z.Ct else 0) + N * 8
+        return N * 4 + c * (8 + Cv * 4) + V * Cv * 4 + T * 12 + (c * 8 if z.Ct else 0) + c * 8
     if name == "k_interp_bwd_bary":
-        return z.Vuv * 8 + T * 12 + N * 12 + N * 8 + N * 8
+        return z.Vuv * 8 + T * 12 + N * 4 + c * (8 + 8) + c * 8
     if name == "k_interp_bwd_vertex":
         return z.adj + V * Cv * 4
     if name == "k_rast_bwd_tile":
-        return B * V * 16 + T * 12 + N * (4 + 8 + d)
+        return B * V * 16 + T * 12 + N * 4 + c * (8 + d)
     if name == "k_rast_bwd_vertex":
         return z.adj + B * V * 16 + B * V * 16
     if name == "k_fragsort":
         return N * 4
     if name == "k_transform":
-        return V * 12 + B * 64 + B * V * 16
+        return cb["transform"]
     if name == "k_transform_bwd":
-        return B * V * 16 + B * 64 + V * 12
+        return cb["transform_bwd"]
     if name == "k_vertex_attrs":
-        return V * 12 + T * 12 + z.adj + (V * 12 if z.ex else 0) + V * Cv * 4
+        return cb["vertex_attrs"]
     if name == "k_shade_bwd" and not z.env:
-        sh_in = N * 4 + N * 6 * 4 + (N * z.Ct * 4 if z.Ct else N * 12) + B * 12
-        return sh_in + N * 12 + N * 6 * 4 + (N * z.Ct * 4 if z.Ct else N * 12)
+        return cb["shade_bwd"]
     if name == "k_shade" and not z.env:
-        return N * 4 + N * 6 * 4 + (N * z.Ct * 4 if z.Ct else N * 12) + B * 12 + N * 12
+        return cb["shade"]
     return None
 
 
@@ -562,6 +572,62 @@ def copy_bandwidth(mib: int = 1024, reps: int = 20) -> dict:
             "ms_per_copy": round(ms, 4), "kind": "torch copy_ (device to device), read + write"}
 
 
+def _log(msg):
+    """One progress line per finished phase, on stderr (stdout carries the
+    single JSON result line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def oracle_rate(scene, seconds, threads, views=None, view_threads=1, max_steps=200):
+    """Times the C oracle's whole fwd+bwd step (forward of the current scene,
+    loss against the target, backward) on the host: `threads` OpenMP threads
+    and row bands inside each step, or `view_threads` Python threads taking a
+    view each (the oracle's C calls release the interpreter lock).  Returns
+    (ms per step, steps run, pixels per step)."""
+    import oracle
+    from oracle import step as ostep
+    from concurrent.futures import ThreadPoolExecutor
+    n = scene.mvp.shape[0]
+    sel = list(range(n)) if views is None else list(views)
+    oracle.set_threads(threads)
+    try:
+        if view_threads > 1:
+            with ThreadPoolExecutor(view_threads) as ex:
+                tg = dict(zip(sel, ex.map(lambda v: ostep.forward(scene, slice(v, v + 1), target=True)["rgba"],
+                                          sel)))
+        else:
+            tg = {None: ostep.forward(scene, None if views is None else slice(sel[0], sel[-1] + 1),
+                                      target=True, threads=threads)["rgba"]}
+
+        def one(v):
+            sl = slice(v, v + 1) if v is not None else (None if views is None else slice(sel[0], sel[-1] + 1))
+            o = ostep.forward(scene, sl, threads=threads)
+            ostep.backward(scene, o, tg[v])
+
+        t0 = time.perf_counter()
+        nrun = 0
+        while True:
+            if view_threads > 1:
+                with ThreadPoolExecutor(view_threads) as ex:
+                    list(ex.map(one, sel))
+            else:
+                one(None)
+            nrun += 1
+            if time.perf_counter() - t0 > seconds or nrun >= max_steps:
+                break
+        tc = (time.perf_counter() - t0) / nrun
+    finally:
+        oracle.set_threads(1)
+    return tc * 1e3, nrun, len(sel) * scene.H * scene.W
+
+
+def _ncpu():
+    try:
+        return max(1, min(len(os.sched_getaffinity(0)), 16))
+    except AttributeError:
+        return max(1, min(os.cpu_count() or 1, 16))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -600,6 +666,7 @@ def main():
     B = scene.mvp.shape[0]
     m = measure(scene, args.steps, args.warmup, -1 if args.only_graph else args.profile_steps)
     ms_batched = m["ms_per_step"]
+    _log(f"config {args.config}: {ms_batched:.4f} ms/step")
     if args.only_graph:
         print(json.dumps({"ms_per_step": ms_batched}))
         return
@@ -625,7 +692,13 @@ def main():
         z3 = Shapes(m3["step"], m3["cov"])
         b3 = sum(call_bytes(z3).values())
         pix3 = s3.mvp.shape[0] * s3.H * s3.W
+        # the same 16 views with the full form of the layers (graph replays only)
+        s3f, _ = scene_for(3)
+        s3f.extra["band"] = False
+        ms_full = measure(s3f, args.multiview_steps, 5, -1)["ms_per_step"]
         multi = {"workload": d3, "views": int(s3.mvp.shape[0]),
+                 "layers": "edge-band form (full layers where the blend's edge mask reaches)",
+                 "full_form_ms_per_step": round(ms_full, 4),
                  "ms_per_step": round(m3["ms_per_step"], 4),
                  "value": round(pix3 / (m3["ms_per_step"] * 1e-3) / 1e6, 2), "unit": "Mpix/s",
                  "tris_per_s": round(s3.mvp.shape[0] * s3.tris.shape[0] / (m3["ms_per_step"] * 1e-3), 1),
@@ -638,9 +711,33 @@ def main():
                              for k, a, b, c in m3["table"][:12]],
                  "launches": [{"launch": k, "ms": round(a, 5)} for k, a in m3["launches"][:16]]}
         del m3
+        _log(f"16 views: {multi['ms_per_step']} ms/step (full form {multi['full_form_ms_per_step']})")
+
+    # ---- the large configuration: 8 views at 2048^2, 1 M triangles ---------
+    large = None
+    if args.large and args.config == 2:
+        s5, d5 = scene_for(5)
+        m5 = measure(s5, 10, 2, 2, plain_steps_min=2)
+        z5 = Shapes(m5["step"], m5["cov"])
+        b5 = sum(call_bytes(z5).values())
+        pix5 = s5.mvp.shape[0] * s5.H * s5.W
+        large = {"workload": d5, "views": int(s5.mvp.shape[0]), "layers": "full form",
+                 "ms_per_step": round(m5["ms_per_step"], 3),
+                 "value": round(pix5 / (m5["ms_per_step"] * 1e-3) / 1e6, 2), "unit": "Mpix/s",
+                 "tris_per_s": round(s5.mvp.shape[0] * s5.tris.shape[0] / (m5["ms_per_step"] * 1e-3), 1),
+                 "plain_ms_per_step": round(m5["plain_ms_per_step"], 3),
+                 "batched_vs_plain_speedup": round(m5["plain_ms_per_step"] / m5["ms_per_step"], 3),
+                 "step_alg_bytes": b5,
+                 "step_hbm_frac": round(b5 / (m5["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                 "kernels": [{"kernel": k, "ms_per_step": round(a, 4), "launches_per_step": c}
+                             for k, a, b, c in m5["table"][:12]]}
+        del m5
+        _log(f"large: {large['ms_per_step']} ms/step")
 
     # ---- the uneven 64-instance batch beside its per-instance form ---------
     uneven = uneven_line(args.uneven_steps, max(1, args.profile_steps // 4)) if args.uneven and args.config == 2 else None
+    if uneven:
+        _log(f"uneven: {uneven['ms_per_step']} ms/step")
 
     # ---- the two-stage fit of the cross-platform application ---------------
     fit = None
@@ -648,6 +745,7 @@ def main():
         from paper_2204_01386_amd import scenes as _sc
         from paper_2204_01386_amd.fit import run_fit
         fr = run_fit(_sc.fit_scene())
+        _log(f"fit: {fr['ms_per_iteration']} ms/iteration")
         c = fr["curve"]
         first = next(x for x in c if x["stage"] == "silhouette")
         last_sil = [x for x in c if x["stage"] == "silhouette"][-1]
@@ -664,6 +762,7 @@ def main():
     if args.fit and args.config == 2:
         from paper_2204_01386_amd.fit import run_env_fit
         er = run_env_fit()
+        _log(f"environment-map fit: {er['ms_per_iteration']} ms/iteration")
         c0, c1 = er["curve"][0], er["curve"][-1]
         pbs = {"workload": er["workload"], "iterations": er["iterations"], "ms_per_iteration": er["ms_per_iteration"],
                "loss": [c0["loss"], c1["loss"]], "env_rel_error": [c0["env_rel_error"], c1["env_rel_error"]],
@@ -673,21 +772,47 @@ def main():
     # ---- CPU baseline: the oracle's step on the same workload --------------
     cpu = None
     if not args.no_cpu:
-        from oracle import step as ostep
-        otgt = ostep.forward(scene, target=True)["rgba"]
-        t0 = time.perf_counter()
-        nrun = 0
-        while True:
-            o = ostep.forward(scene)
-            ostep.backward(scene, o, otgt)
-            nrun += 1
-            if time.perf_counter() - t0 > args.cpu_seconds or nrun >= 200:
-                break
-        tc = (time.perf_counter() - t0) / nrun
-        cpu = {"value": round(B * scene.H * scene.W / tc / 1e6, 4), "unit": "Mpix/s", "cores": 1,
-               "kind": "oracle",
-               "sample": f"{nrun} full fwd+bwd steps of the same workload (C oracle, fp64, "
-                         f"single thread), {tc * 1e3:.1f} ms/step, on {_host_cpu()}"}
+        nc = _ncpu()
+        ms1, n1, px = oracle_rate(scene, args.cpu_seconds, 1)
+        _log(f"oracle, one core: {ms1:.1f} ms/step")
+        msa, na, _ = oracle_rate(scene, args.cpu_seconds, nc)
+        _log(f"oracle, {nc} threads: {msa:.1f} ms/step")
+        cpu = {"value": round(px / (msa * 1e-3) / 1e6, 4), "unit": "Mpix/s", "cores": nc, "kind": "oracle",
+               "sample": f"{na} full fwd+bwd steps of the same workload (C oracle, fp64), {msa:.1f} ms/step "
+                         f"with {nc} threads (OpenMP per-pixel and per-texel loops, rasterization in row bands), "
+                         f"on {_host_cpu()}",
+               "single_core": {"value": round(px / (ms1 * 1e-3) / 1e6, 4), "unit": "Mpix/s", "cores": 1,
+                               "sample": f"{n1} steps, {ms1:.1f} ms/step, one thread"}}
+        if multi:
+            s3, _ = scene_for(3)
+            ms1, n1, px1 = oracle_rate(s3, 1.0, 1, views=range(2))
+            _log(f"oracle, 16 views sample, one core: {ms1:.0f} ms/step")
+            msa, na, pxa = oracle_rate(s3, 1.0, 1, view_threads=nc)
+            _log(f"oracle, 16 views, {nc} threads: {msa:.0f} ms/step")
+            multi["cpu_baseline"] = {
+                "value": round(pxa / (msa * 1e-3) / 1e6, 4), "unit": "Mpix/s", "cores": nc, "kind": "oracle",
+                "sample": f"{na} steps of all 16 views, one view per thread, {msa:.0f} ms/step",
+                "single_core": {"value": round(px1 / (ms1 * 1e-3) / 1e6, 4), "unit": "Mpix/s", "cores": 1,
+                                "sample": f"{n1} steps of views 1-2, one thread, {ms1:.0f} ms/step"}}
+        if uneven:
+            from paper_2204_01386_amd import scenes as _sc
+            sub = _sc.config4()[:8]
+            tms1 = tmsa = px1 = pxa = 0.0
+            for sc in sub[:2]:
+                m_, _, p_ = oracle_rate(sc, 0.0, 1)
+                tms1, px1 = tms1 + m_, px1 + p_
+            from concurrent.futures import ThreadPoolExecutor
+            t0 = time.perf_counter()
+            with ThreadPoolExecutor(nc) as ex:
+                pxa = sum(p_ for _, _, p_ in ex.map(lambda sc: oracle_rate(sc, 0.0, 1), sub))
+            tmsa = (time.perf_counter() - t0) * 1e3
+            uneven["cpu_baseline"] = {
+                "value": round(pxa / (tmsa * 1e-3) / 1e6, 4), "unit": "Mpix/s", "cores": nc, "kind": "oracle",
+                "sample": f"one step of instances 1-8 ({pxa / 1e6:.2f} Mpix), one instance per thread, "
+                          f"{tmsa:.0f} ms",
+                "single_core": {"value": round(px1 / (tms1 * 1e-3) / 1e6, 4), "unit": "Mpix/s", "cores": 1,
+                                "sample": f"one step of instances 1-2 ({px1 / 1e6:.2f} Mpix), one thread, "
+                                          f"{tms1:.0f} ms"}}
 
     pix = B * scene.H * scene.W
     cbw = copy_bandwidth()
@@ -699,6 +824,8 @@ def main():
         multi["step_copy_frac"] = copy_frac(multi["step_alg_bytes"], multi["ms_per_step"])
     if uneven and uneven.get("step_alg_bytes"):
         uneven["step_copy_frac"] = copy_frac(uneven["step_alg_bytes"], uneven["ms_per_step"])
+    if large:
+        large["step_copy_frac"] = copy_frac(large["step_alg_bytes"], large["ms_per_step"])
     res = {
         "metric": "fwd+bwd Mpix/s & tris/s at 512^2 80k tris; batched vs plain speedup, %HBM roofline",
         "value": round(pix / (ms_batched * 1e-3) / 1e6, 3),
@@ -740,6 +867,7 @@ def main():
         "pbs_env_fit": pbs,
         "multiview": multi,
         "uneven": uneven,
+        "large": large,
         "kernels": kernel_rows,
         "launches": launch_rows,
     }

@@ -24,7 +24,7 @@ BLEND_HSR, BLEND_AA, BLEND_SOFTRAS, BLEND_HARD = 0, 1, 2, 3
 
 def build(openmp: bool = False) -> str:
     """Compile liboracle.so with gcc (no contraction, no fast-math)."""
-    cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
+    cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
            "-shared", "-fPIC", "-o", LIB, SRC, "-lm"]
     subprocess.check_call(cmd)
     return LIB
@@ -39,7 +39,15 @@ def lib():
         if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
             build()
         _lib = C.CDLL(LIB)
+        _lib.orc_set_threads.argtypes = [C.c_int]
+        _lib.orc_set_threads(1)
     return _lib
+
+
+def set_threads(n: int) -> int:
+    """Threads of the oracle's per-pixel and per-texel loops (1 unless a
+    timing asks for more; results do not depend on it)."""
+    return int(lib().orc_set_threads(int(n)))
 
 
 class _TexDesc(C.Structure):

@@ -28,6 +28,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #include "oracle.h"
 
@@ -708,6 +711,7 @@ int orc_texture(const double *tex, const orc_tex_desc *td, const float *coord,
 {
     int cd = td->kind == ORC_TEX_CUBE ? 3 : 2;
     int Ct = td->Ct;
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < N; i++) {
         double *y = out + i * Ct;
         for (int c = 0; c < Ct; c++) y[c] = 0.0;
@@ -732,6 +736,7 @@ int orc_texture_bwd_coord(const double *tex, const orc_tex_desc *td, const float
 {
     int cd = td->kind == ORC_TEX_CUBE ? 3 : 2;
     int Ct = td->Ct;
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < N; i++) {
         double *gc = grad_coord + i * cd;
         for (int j = 0; j < cd; j++) gc[j] = 0.0;
@@ -825,6 +830,7 @@ int orc_texture_bwd_tex(const orc_tex_desc *td, const float *coord, const int32_
     int wv = td->kind == ORC_TEX_CUBE ? ORC_WRAP_CLAMP : td->wrap_v;
     int64_t cells = (int64_t)F * Ht * Wt;
     memset(grad_tex, 0, sizeof(double) * (size_t)cells * Ct);
+#pragma omp parallel for collapse(2) schedule(static)
     for (int f = 0; f < F; f++)
         for (int ty = 0; ty < Ht; ty++)
             for (int tx = 0; tx < Wt; tx++) {
@@ -958,6 +964,7 @@ int orc_softras(const double *color, const double *dist, const int32_t *tri_id,
     int rc = orc_edge_mask(tri_id, dist, B, K, H, W, delta, mode, E);
     if (rc) return rc;
     int64_t N = (int64_t)H * W;
+#pragma omp parallel for collapse(2) schedule(static)
     for (int b = 0; b < B; b++)
         for (int64_t p = 0; p < N; p++) {
             int64_t q = (int64_t)b * N + p;
@@ -996,6 +1003,7 @@ int orc_softras_bwd(const double *color, const double *dist, const int32_t *tri_
     int64_t N = (int64_t)H * W;
     memset(grad_layer_color, 0, sizeof(double) * (size_t)B * K * N * Cc);
     if (grad_dist) memset(grad_dist, 0, sizeof(double) * (size_t)B * K * N);
+#pragma omp parallel for collapse(2) schedule(static)
     for (int b = 0; b < B; b++)
         for (int64_t p = 0; p < N; p++) {
             int64_t q = (int64_t)b * N + p;
@@ -1184,6 +1192,7 @@ static void nmap_fwd(const double *n, const double *t, const double *m, double *
 int orc_normal_map(const double *n, const double *t, const double *m, const int32_t *tri_id,
                    int64_t N, double *out)
 {
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < N; i++) {
         double nh[3], tp[3], th[3], bh[3], u[3];
         if (tri_id[i] < 0) { out[3 * i] = out[3 * i + 1] = out[3 * i + 2] = 0.0; continue; }
@@ -1195,6 +1204,7 @@ int orc_normal_map(const double *n, const double *t, const double *m, const int3
 int orc_normal_map_bwd(const double *n, const double *t, const double *m, const int32_t *tri_id,
                        int64_t N, const double *g, double *gn, double *gt, double *gm)
 {
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < N; i++) {
         const double *ni = n + 3 * i, *ti = t + 3 * i, *mi = m + 3 * i;
         double *gni = gn + 3 * i, *gti = gt + 3 * i, *gmi = gm + 3 * i;
@@ -1240,6 +1250,7 @@ static const double LIGHT[3] = {0.40824829046386302, 0.40824829046386302, 0.8164
 int orc_reflect(const double *n, const double *pos, const double *eye, const int32_t *tri_id,
                 int B, int64_t Npv, double *out)
 {
+#pragma omp parallel for collapse(2) schedule(static)
     for (int b = 0; b < B; b++)
         for (int64_t j = 0; j < Npv; j++) {
             int64_t i = (int64_t)b * Npv + j;
@@ -1259,6 +1270,7 @@ int orc_reflect(const double *n, const double *pos, const double *eye, const int
 int orc_reflect_bwd(const double *n, const double *pos, const double *eye, const int32_t *tri_id,
                     int B, int64_t Npv, const double *g, double *gn, double *gpos)
 {
+#pragma omp parallel for collapse(2) schedule(static)
     for (int b = 0; b < B; b++)
         for (int64_t j = 0; j < Npv; j++) {
             int64_t i = (int64_t)b * Npv + j;
@@ -1354,6 +1366,7 @@ int orc_shade(int mode, const double *n, const double *pos, const double *albedo
               const double *env, const double *eye, const int32_t *tri_id, int B, int64_t Npv,
               double *out)
 {
+#pragma omp parallel for collapse(2) schedule(static)
     for (int b = 0; b < B; b++)
         for (int64_t j = 0; j < Npv; j++) {
             int64_t i = (int64_t)b * Npv + j;
@@ -1369,6 +1382,7 @@ int orc_shade_bwd(int mode, const double *n, const double *pos, const double *al
                   const double *env, const double *eye, const int32_t *tri_id, int B, int64_t Npv,
                   const double *g, double *gn, double *gpos, double *galb, double *genv)
 {
+#pragma omp parallel for collapse(2) schedule(static)
     for (int b = 0; b < B; b++)
         for (int64_t j = 0; j < Npv; j++) {
             int64_t i = (int64_t)b * Npv + j;
@@ -1494,4 +1508,18 @@ int orc_texture_f32(const float *tex, const orc_tex_desc *td, const float *coord
         }
     }
     return 0;
+}
+
+/* Threads of the per-pixel and per-texel loops (OpenMP; each output element
+ * is computed by one thread in a fixed order, so results do not depend on
+ * the count).  Test runs keep one; the CPU baseline times all host cores. */
+int orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    omp_set_num_threads(n > 0 ? n : 1);
+    return n > 0 ? n : 1;
+#else
+    (void)n;
+    return 1;
+#endif
 }

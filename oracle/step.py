@@ -41,7 +41,50 @@ def banded(scene):
     return scene.r > 0 and blend in ("hsr", "aa") and bool(scene.extra.get("band", True))
 
 
-def forward(scene, views=None, target=False, window=None):
+def _bands(y0, h, threads):
+    """Row bands (y, rows) splitting rows y0 .. y0 + h - 1 into `threads` parts."""
+    n = max(1, min(int(threads), h))
+    cuts = [y0 + (h * i) // n for i in range(n + 1)]
+    return [(a, b - a) for a, b in zip(cuts[:-1], cuts[1:]) if b > a]
+
+
+def _raster(pc, tris, H, W, K, r, window, threads):
+    """The oracle's rasterization of the window (or image); with threads > 1,
+    row bands of it in a thread pool (its C calls release the interpreter
+    lock), concatenated: the same layers, for timing on all host cores."""
+    x0, y0, w, h = window if window is not None else (0, 0, W, H)
+    if threads <= 1:
+        if window is None:
+            return O.rasterize(pc, tris, H, W, K=K, r=r)
+        return O.rasterize_window(pc, tris, H, W, window, K=K, r=r)
+    from concurrent.futures import ThreadPoolExecutor
+    bands = _bands(y0, h, threads)
+    with ThreadPoolExecutor(len(bands)) as ex:
+        parts = list(ex.map(lambda b: O.rasterize_window(pc, tris, H, W, (x0, b[0], w, b[1]), K=K, r=r), bands))
+    return tuple(np.concatenate([p[i] for p in parts], axis=2) for i in range(4))
+
+
+def _raster_bwd(pc, tris, tid, hard, g_bary, g_dist, image, window, threads):
+    """The rasterization adjoint; with threads > 1, row bands in a thread
+    pool whose window adjoints are summed (the adjoint is a sum over
+    fragments)."""
+    H, W = image
+    x0, y0, w, h = window if window is not None else (0, 0, W, H)
+    if threads <= 1:
+        return O.rasterize_bwd(pc, tris, tid, hard, g_bary, g_dist, image=image, window=window)
+    from concurrent.futures import ThreadPoolExecutor
+    bands = _bands(y0, h, threads)
+
+    def one(b):
+        rows = slice(b[0] - y0, b[0] - y0 + b[1])
+        cut = lambda a: None if a is None else np.ascontiguousarray(a[:, :, rows])
+        return O.rasterize_bwd(pc, tris, cut(tid), cut(hard), cut(g_bary), cut(g_dist), image=image,
+                               window=(x0, b[0], w, b[1]))
+    with ThreadPoolExecutor(len(bands)) as ex:
+        return sum(ex.map(one, bands))
+
+
+def forward(scene, views=None, target=False, window=None, threads=1):
     """Forward of the scene's views.  window = (x0, y0, w, h): only the
     pixels of that rectangle of each H x W image (every triangle considered;
     the edge mask is exact where its boundary test and dilation stay inside
@@ -64,10 +107,7 @@ def forward(scene, views=None, target=False, window=None):
         extra = np.asarray(scene.extra["tangent"], np.float64)
     vattr = np.concatenate([n, st["pos"]] + ([extra] if extra is not None else []), 1)
     pc = O.transform_f32(pos32, mvp)
-    if window is None:
-        tid, hard, bary, dist = O.rasterize(pc, tris, H, W, K=K, r=r)
-    else:
-        tid, hard, bary, dist = O.rasterize_window(pc, tris, H, W, window, K=K, r=r)
+    tid, hard, bary, dist = _raster(pc, tris, H, W, K, r, window, threads)
     # the blend setting of §3.4.3: HardSoftRas with delta = r by default; a
     # scene may choose the anti-aliasing or SoftRas-like settings instead
     blend = {"hsr": O.BLEND_HSR, "aa": O.BLEND_AA, "softras": O.BLEND_SOFTRAS,
@@ -82,7 +122,7 @@ def forward(scene, views=None, target=False, window=None):
     b32 = bary.astype(np.float32)
     gs = O.interpolate_f32(vattr.astype(np.float32), tris, tid, b32).astype(np.float64)
     st.update(vattr=vattr, pc=pc, tid=tid, hard=hard, bary=bary, dist=dist if r > 0 else None, gbuf=gb,
-              gshade=gs, image=(H, W), window=window)
+              gshade=gs, image=(H, W), window=window, threads=threads)
     nrm = gs[..., 0:3]
     p = gs[..., 3:6]
     if mode == O.SHADE_LAMBERT:
@@ -161,8 +201,8 @@ def backward(scene, st, target_rgba=None, grad_rgba=None):
         _, g_bary_uv = O.interpolate_bwd(scene.uv, scene.uv_tris, tid, st["bary"], g_uv)
     g_vattr, g_bary = O.interpolate_bwd(st["vattr"], tris, tid, st["bary"], g_gbuf)
     g_bary = g_bary + g_bary_uv
-    g_clip = O.rasterize_bwd(st["pc"], tris, tid, st["hard"], g_bary, O_grad_dist(gd, st),
-                             image=st["image"], window=st["window"])
+    g_clip = _raster_bwd(st["pc"], tris, tid, st["hard"], g_bary, O_grad_dist(gd, st), st["image"],
+                         st["window"], st["threads"])
     out["clip"] = g_clip
     g_pos = O.transform_bwd(st["mvp"], g_clip)
     g_pos += O.vertex_normals_bwd(st["pos"], tris, g_vattr[:, 0:3]) + g_vattr[:, 3:6]
