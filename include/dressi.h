@@ -144,11 +144,16 @@ int dressi_check_status(dressi_ctx *ctx, int64_t *needed, void *stream);
  *   outputs only at non-empty slots, so a pipeline built from them gets the
  *   same results either way and skips the zero stores (most slots of the
  *   deeper layers are empty).  Changes which bytes are written, never a
- *   value at a non-empty slot. */
+ *   value at a non-empty slot.
+ * DRESSI_TUNE_IV_ROWS: texel rows per lane of the inverse-UV gather of
+ *   dressi_texture_bwd and dressi_texture_grad_invuv: 1, 2 or 4 (0 =
+ *   automatic).  Each workgroup covers 16 x 16*rows texels; every choice
+ *   adds the same terms in the same order. */
 #define DRESSI_TUNE_BIN_CAPACITY 1
 #define DRESSI_TUNE_HARD_RASTER 2
 #define DRESSI_TUNE_HYBRID_WEIGHT 3
 #define DRESSI_TUNE_EMPTY_SLOTS 4
+#define DRESSI_TUNE_IV_ROWS 5
 int dressi_tune(dressi_ctx *ctx, int key, int64_t value);
 
 /* Kernel timing for measurement: while on, every kernel launch of the library
@@ -480,6 +485,59 @@ int dressi_shade_bwd(dressi_ctx *ctx, int mode, const dressi_frag_in *in, const 
 int dressi_loss_l2(dressi_ctx *ctx, const float *color, const float *sil, const float *target,
                    const float *weight, int B, int H, int W, float *loss, float *grad_color,
                    float *grad_sil, void *stream);
+
+/* ----------------------------------------------------------------------------
+ * Stage packing of a single-layer hard image (§3.3.3: the per-fragment
+ * function objects of one image size packed into one pass, so that only the
+ * values used beyond the pass are written).  K = 1, no blend edge (the hard
+ * blend: the image is the front fragment's colour where one is present).
+ * Shading: DRESSI_SHADE_LAMBERT with per-vertex normal, position and colour
+ * (Cv = 9), or DRESSI_SHADE_PHONG with per-vertex normal and position (Cv = 6),
+ * per-corner texture coordinates and a 2-D RGBA albedo texture.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    int mode;                 /* DRESSI_SHADE_LAMBERT or DRESSI_SHADE_PHONG */
+    const float *vattr;       /* [V, Cv] per-vertex attributes (dressi_vertex_attrs) */
+    int V, Cv;
+    const int32_t *tris;      /* [T, 3] */
+    int T;
+    const float *uv;          /* Phong: [Vuv, 2] texture coordinates, indexed by uv_tris [T, 3] */
+    const int32_t *uv_tris;
+    int Vuv;
+    const float *tex;         /* Phong: [Ht, Wt, 4] albedo (kind 2-D, Ct = 4), 16-byte aligned */
+    dressi_tex_desc td;
+    const float *eye;         /* [B, 3] camera positions */
+} dressi_packed_scene;
+
+/* Forward of the packed pass over B views of H x W (tri_id [B,H,W] and bary
+ * [B,H,W,2] from dressi_rasterize with K = 1, r = 0).  Writes the same values
+ * as dressi_interpolate (vattr -> gbuf [B,H,W,Cv]; Phong: uv -> uvbuf
+ * [B,H,W,2]), dressi_texture (Phong: tex -> samp [B,H,W,4], 16-byte aligned),
+ * dressi_shade and dressi_softras with BLEND_HARD (color [B,H,W,3], sil
+ * [B,H,W], edge [B,H,W] = 0) in sequence; under DRESSI_TUNE_EMPTY_SLOTS = 1
+ * the gbuf, uvbuf and samp entries of empty pixels are left unwritten.
+ * inv (Phong, nullable): the inverse-UV map [B, Ht, Wt] int32 of the
+ * backward, 16-byte aligned, set to -1 here. */
+int dressi_packed_forward(dressi_ctx *ctx, const dressi_packed_scene *scene, const int32_t *tri_id,
+                          const float *bary, int B, int H, int W, float *gbuf, float *uvbuf, float *samp,
+                          float *color, float *sil, uint8_t *edge, int32_t *inv, void *stream);
+/* Backward of the packed pass with the L2 loss of dressi_loss_l2 (uniform
+ * weight) against target [B,H,W,4]: loss [1] (its partial sums grouped by 256
+ * pixels, so it may differ from dressi_loss_l2's in the last bits);
+ * grad_color, grad_sil (nullable) as dressi_loss_l2 writes them; grad_gbuf
+ * [B,H,W,Cv] and, Phong, grad_samp [B,H,W,4] as dressi_softras_bwd and
+ * dressi_shade_bwd give them (normal, position and, Lambert, colour at the
+ * gbuf's offsets); Phong: grad_bary_uv [B,H,W,2], the barycentric gradient
+ * through the texture coordinate (dressi_texture_bwd's coordinate gradient
+ * fed to dressi_interpolate_bwd of uv), and, when inv is given (as set by
+ * dressi_packed_forward), every covered pixel registered in it as
+ * dressi_invuv_build does: dressi_texture_grad_invuv then gives the texture
+ * gradient.  Inputs are the forward's outputs. */
+int dressi_packed_backward(dressi_ctx *ctx, const dressi_packed_scene *scene, const int32_t *tri_id, int B,
+                           int H, int W, const float *gbuf, const float *uvbuf, const float *samp,
+                           const float *color, const float *sil, const float *target, float *loss,
+                           float *grad_color, float *grad_sil, float *grad_gbuf, float *grad_samp,
+                           float *grad_bary_uv, int32_t *inv, void *stream);
 
 /* ----------------------------------------------------------------------------
  * The optimisation loop around the step (§4.1: vertex positions fitted to

@@ -26,7 +26,7 @@ if not os.path.exists(LIB_PATH):
 _lib = C.CDLL(LIB_PATH)
 
 TEX_2D, TEX_CUBE, TEX_2D_ARRAY = 0, 1, 2
-TUNE_BIN_CAPACITY, TUNE_HARD_RASTER, TUNE_HYBRID_WEIGHT, TUNE_EMPTY_SLOTS = 1, 2, 3, 4
+TUNE_BIN_CAPACITY, TUNE_HARD_RASTER, TUNE_HYBRID_WEIGHT, TUNE_EMPTY_SLOTS, TUNE_IV_ROWS = 1, 2, 3, 4, 5
 WRAP_REPEAT, WRAP_CLAMP = 0, 1
 BLEND_HSR, BLEND_AA, BLEND_SOFTRAS, BLEND_HARD = 0, 1, 2, 3
 
@@ -50,6 +50,12 @@ class FragIn(C.Structure):
                 ("tangent", _vp), ("tangent_stride", _i), ("nmap", _vp), ("nmap_stride", _i),
                 ("albedo", _vp), ("albedo_stride", _i), ("albedo_channels", _i),
                 ("env", _vp), ("env_stride", _i), ("tri_eye", _vp)]
+
+
+class PackedScene(C.Structure):
+    """dressi_packed_scene: the inputs of the packed single-layer pass."""
+    _fields_ = [("mode", _i), ("vattr", _vp), ("V", _i), ("Cv", _i), ("tris", _vp), ("T", _i),
+                ("uv", _vp), ("uv_tris", _vp), ("Vuv", _i), ("tex", _vp), ("td", TexDesc), ("eye", _vp)]
 
 
 class FragGrad(C.Structure):
@@ -111,6 +117,9 @@ _SIG = {
     "dressi_shade": [_vp, _i, _vp, _vp, _vp, _i, _i64, _vp, _vp, _vp],
     "dressi_shade_bwd": [_vp, _i, _vp, _vp, _vp, _i, _i64, _vp, _vp, _vp, _vp],
     "dressi_loss_l2": [_vp, _vp, _vp, _vp, _vp, _i, _i, _i, _vp, _vp, _vp, _vp],
+    "dressi_packed_forward": [_vp, _vp, _vp, _vp, _i, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
+    "dressi_packed_backward": [_vp, _vp, _vp, _i, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                               _vp, _vp, _vp, _vp],
     "dressi_transform_batched": [_vp, _vp, _vp, _vp, _i, _vp, _vp],
     "dressi_tune": [_vp, _i, _i64],
     "dressi_transform_batched_bwd": [_vp, _vp, _vp, _i, _vp, _vp, _vp],

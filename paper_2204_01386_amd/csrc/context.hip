@@ -139,6 +139,11 @@ extern "C" int dressi_tune(dressi_ctx *ctx, int key, int64_t value) {
         if (value != 0 && value != 1) return dressi_fail(ctx, DRESSI_EINVAL, "tune: empty slots is 0 or 1");
         ctx->skip_empty = (int)value;
         return DRESSI_OK;
+    case DRESSI_TUNE_IV_ROWS:
+        if (value != 0 && value != 1 && value != 2 && value != 4)
+            return dressi_fail(ctx, DRESSI_EINVAL, "tune: gather rows is 0, 1, 2 or 4");
+        ctx->iv_rows = (int)value;
+        return DRESSI_OK;
     default:
         return dressi_fail(ctx, DRESSI_EINVAL, "tune: unknown key");
     }

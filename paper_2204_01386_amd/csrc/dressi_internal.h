@@ -23,6 +23,7 @@ struct dressi_ctx {
     int hard_raster = 0;        // hard rasterization: 0 triangle-parallel, 1 pixel-parallel, 2 per tile
     int hybrid_weight = 24;     // strategy 2's cost ratio, in sixteenths
     int skip_empty = 0;         // 1: per-fragment outputs of empty slots left unwritten
+    int iv_rows = 0;            // texel rows per lane of the inverse-UV gather (0 = automatic)
     int64_t *status = nullptr;  // device: [0] overflow flag, [1] bin capacity needed
     int32_t *counters = nullptr;  // device counters kept at zero between calls
     size_t counters_n = 0;

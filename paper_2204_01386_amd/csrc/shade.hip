@@ -6,7 +6,7 @@
 // vertex's corners split over a fixed group of lanes combined in a fixed
 // order, and the loss is reduced in a fixed tree order, so every result is
 // bitwise reproducible.
-#include "dressi_internal.h"
+#include "texcore.h"
 
 // ---------------------------------------------------------------------------
 // transform
@@ -386,6 +386,16 @@ __device__ __forceinline__ void shade_forward(int mode, const dressi_frag_in &in
     if (mode == DRESSI_SHADE_PHONG_ENV && in.env) s.e = ldd3(in.env + i * in.env_stride);
 }
 
+// The colour of a shaded fragment, rounded once to float.
+__device__ __forceinline__ void shade_color(int mode, const ShadeState &s, float *c) {
+    double add = 0.0;
+    if (mode != DRESSI_SHADE_LAMBERT) add = 0.2 * s.a[3] * s.spec;
+    const double env = mode == DRESSI_SHADE_PHONG_ENV ? 0.5 * s.a[3] : 0.0;
+    c[0] = (float)(s.a[0] * s.base + add + env * s.e.x);
+    c[1] = (float)(s.a[1] * s.base + add + env * s.e.y);
+    c[2] = (float)(s.a[2] * s.base + add + env * s.e.z);
+}
+
 __global__ void k_shade(int mode, dressi_frag_in in, const float *__restrict__ eye,
                         const int32_t *__restrict__ tri_id, int64_t N, int64_t Npv,
                         float *__restrict__ color, float *__restrict__ dir, int skip_empty) {
@@ -404,14 +414,7 @@ __global__ void k_shade(int mode, dressi_frag_in in, const float *__restrict__ e
         const d3 d = (2.0 * dotd(s.np, s.vh)) * s.np - s.vh;
         dir[3 * i] = (float)d.x; dir[3 * i + 1] = (float)d.y; dir[3 * i + 2] = (float)d.z;
     }
-    if (color) {
-        double add = 0.0;
-        if (mode != DRESSI_SHADE_LAMBERT) add = 0.2 * s.a[3] * s.spec;
-        const double env = mode == DRESSI_SHADE_PHONG_ENV ? 0.5 * s.a[3] : 0.0;
-        color[3 * i] = (float)(s.a[0] * s.base + add + env * s.e.x);
-        color[3 * i + 1] = (float)(s.a[1] * s.base + add + env * s.e.y);
-        color[3 * i + 2] = (float)(s.a[2] * s.base + add + env * s.e.z);
-    }
+    if (color) shade_color(mode, s, color + 3 * i);
 }
 
 __device__ __forceinline__ void st3(float *p, int64_t i, int stride, d3 v) {
@@ -419,31 +422,13 @@ __device__ __forceinline__ void st3(float *p, int64_t i, int stride, d3 v) {
     q[0] = (float)v.x; q[1] = (float)v.y; q[2] = (float)v.z;
 }
 
-__global__ void k_shade_bwd(int mode, dressi_frag_in in, const float *__restrict__ eye,
-                            const int32_t *__restrict__ tri_id, int64_t N, int64_t Npv,
-                            const float *__restrict__ grad_color, const float *__restrict__ grad_dir,
-                            dressi_frag_grad gr, int skip_empty) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
+// Adjoint of one covered fragment's shading: the gradient g of its colour
+// (and grad_dir, NULL = 0, of its environment direction) to every non-NULL
+// member of gr at fragment i; s is the fragment's forward state.
+__device__ __forceinline__ void shade_bwd_frag(int mode, const dressi_frag_in &in, const ShadeState &s, d3 g,
+                                               const float *__restrict__ grad_dir, const dressi_frag_grad &gr,
+                                               int64_t i, bool need_geo) {
     const d3 Z{0.0, 0.0, 0.0};
-    if (tri_id[i] < 0) {
-        if (skip_empty) return;
-        if (gr.normal) st3(gr.normal, i, gr.normal_stride, Z);
-        if (gr.pos) st3(gr.pos, i, gr.pos_stride, Z);
-        if (gr.tangent) st3(gr.tangent, i, gr.tangent_stride, Z);
-        if (gr.nmap) st3(gr.nmap, i, gr.nmap_stride, Z);
-        if (gr.env) st3(gr.env, i, gr.env_stride, Z);
-        if (gr.albedo) {
-            float *q = gr.albedo + i * gr.albedo_stride;
-            for (int c = 0; c < in.albedo_channels; c++) q[c] = 0.0f;
-        }
-        return;
-    }
-    const int64_t e = in.tri_eye ? (int64_t)in.tri_eye[tri_id[i]] : i / Npv;
-    bool need_geo = gr.normal || gr.pos || gr.tangent || gr.nmap;
-    ShadeState s;
-    shade_forward(mode, in, eye + 3 * e, i, mode != DRESSI_SHADE_LAMBERT || grad_dir != nullptr, s);
-    const d3 g = grad_color ? ldd3(grad_color + 3 * i) : Z;
     const double gsum = g.x + g.y + g.z;
     if (gr.albedo) {
         float *q = gr.albedo + i * gr.albedo_stride;
@@ -496,6 +481,34 @@ __global__ void k_shade_bwd(int mode, dressi_frag_in in, const float *__restrict
         if (gr.tangent) st3(gr.tangent, i, gr.tangent_stride, Z);
         if (gr.nmap) st3(gr.nmap, i, gr.nmap_stride, Z);
     }
+}
+
+__global__ void k_shade_bwd(int mode, dressi_frag_in in, const float *__restrict__ eye,
+                            const int32_t *__restrict__ tri_id, int64_t N, int64_t Npv,
+                            const float *__restrict__ grad_color, const float *__restrict__ grad_dir,
+                            dressi_frag_grad gr, int skip_empty) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const d3 Z{0.0, 0.0, 0.0};
+    if (tri_id[i] < 0) {
+        if (skip_empty) return;
+        if (gr.normal) st3(gr.normal, i, gr.normal_stride, Z);
+        if (gr.pos) st3(gr.pos, i, gr.pos_stride, Z);
+        if (gr.tangent) st3(gr.tangent, i, gr.tangent_stride, Z);
+        if (gr.nmap) st3(gr.nmap, i, gr.nmap_stride, Z);
+        if (gr.env) st3(gr.env, i, gr.env_stride, Z);
+        if (gr.albedo) {
+            float *q = gr.albedo + i * gr.albedo_stride;
+            for (int c = 0; c < in.albedo_channels; c++) q[c] = 0.0f;
+        }
+        return;
+    }
+    const int64_t e = in.tri_eye ? (int64_t)in.tri_eye[tri_id[i]] : i / Npv;
+    bool need_geo = gr.normal || gr.pos || gr.tangent || gr.nmap;
+    ShadeState s;
+    shade_forward(mode, in, eye + 3 * e, i, mode != DRESSI_SHADE_LAMBERT || grad_dir != nullptr, s);
+    const d3 g = grad_color ? ldd3(grad_color + 3 * i) : Z;
+    shade_bwd_frag(mode, in, s, g, grad_dir, gr, i, need_geo);
 }
 
 static int check_shade(dressi_ctx *ctx, int mode, const dressi_frag_in *in, const float *eye,
@@ -717,5 +730,288 @@ size_t dr_need_shade(const dressi_limits &l) {
     c.take(adjacency_buf_bytes(std::max(l.V, 0), std::max(l.T, 0)));
     c.take(dressi_adjacency_tmp_bytes(std::max(l.V, 0), std::max(l.T, 0)));
     c.take(sizeof(float) * 3 * (size_t)std::max(l.V, 0));
-    return std::max(c.off, sizeof(float) * (size_t)LOSS_MAX_BLOCKS);
+    // the loss partials: LOSS_MAX_BLOCKS (dressi_loss_l2) or one per 256
+    // pixels (dressi_packed_backward)
+    const size_t pix = (size_t)std::max(l.B, 0) * std::max(l.H, 0) * std::max(l.W, 0);
+    return std::max({c.off, sizeof(float) * (size_t)LOSS_MAX_BLOCKS, sizeof(float) * ((pix + 255) / 256)});
+}
+
+// ---------------------------------------------------------------------------
+// packed single-layer pass
+// ---------------------------------------------------------------------------
+// Stage packing (§3.3.3) of a single-layer hard image (K = 1; the blend has
+// no edge, so the image is the front fragment's colour where one is present):
+// one lane per pixel runs the interpolation, texture and shading stages and
+// the blend in the forward, and the loss, blend and shading adjoints, the
+// texture-coordinate adjoint with its inverse-UV registration and the
+// coordinate's barycentric adjoint in the backward.  Every per-fragment
+// value is produced by the same device code as the separate stages.
+
+// Corners of triangle t in a [T, 3] index buffer over Va entries; false when
+// t or a corner is out of range (the stages then give zeros).
+__device__ __forceinline__ bool tri_corners(const int32_t *__restrict__ tris, int T, int Va, int t, int &v0,
+                                            int &v1, int &v2) {
+    v0 = v1 = v2 = -1;
+    if (t >= 0 && t < T) {
+        v0 = tris[3 * (int64_t)t];
+        v1 = tris[3 * (int64_t)t + 1];
+        v2 = tris[3 * (int64_t)t + 2];
+    }
+    return !(v0 < 0 || v0 >= Va || v1 < 0 || v1 >= Va || v2 < 0 || v2 >= Va);
+}
+
+// CV attribute channels (6: normal, position; 9: + colour); TEX: Phong with a
+// 2-D RGBA albedo texture, else Lambert with the vertex colour.
+template <int CV, bool TEX>
+__global__ void __launch_bounds__(256)
+    k_packed_fwd(int mode, dressi_packed_scene sc, const int32_t *__restrict__ tri_id,
+                 const float2 *__restrict__ bary, int64_t npix, int64_t n, float *__restrict__ gbuf,
+                 float *__restrict__ uvbuf, float *__restrict__ samp, float *__restrict__ color,
+                 float *__restrict__ sil, uint8_t *__restrict__ edge, int32_t *__restrict__ inv, int64_t ncells,
+                 int skip_empty) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (inv) {
+        // the backward's inverse-UV map starts at -1 (16-byte aligned, int4 rows)
+        const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+        for (int64_t c = i; c < ncells / 4; c += stride)
+            reinterpret_cast<int4 *>(inv)[c] = make_int4(-1, -1, -1, -1);
+        for (int64_t c = ncells / 4 * 4 + i; c < ncells; c += stride) inv[c] = -1;
+    }
+    if (i >= n) return;
+    const int t = tri_id[i];
+    edge[i] = 0;
+    if (t < 0) {
+        color[3 * i] = 0.0f; color[3 * i + 1] = 0.0f; color[3 * i + 2] = 0.0f;
+        sil[i] = 0.0f;
+        if (skip_empty) return;
+#pragma unroll
+        for (int c = 0; c < CV; c++) gbuf[i * CV + c] = 0.0f;
+        if (TEX) {
+            uvbuf[2 * i] = 0.0f; uvbuf[2 * i + 1] = 0.0f;
+            reinterpret_cast<float4 *>(samp)[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        }
+        return;
+    }
+    const float2 w = bary[i];
+    const float w2 = 1.0f - w.x - w.y;
+    int v0, v1, v2;
+    float ga[CV];
+    if (tri_corners(sc.tris, sc.T, sc.V, t, v0, v1, v2)) {
+        const float *a0 = sc.vattr + (int64_t)v0 * CV, *a1 = sc.vattr + (int64_t)v1 * CV,
+                    *a2 = sc.vattr + (int64_t)v2 * CV;
+#pragma unroll
+        for (int c = 0; c < CV; c++) ga[c] = w.x * a0[c] + w.y * a1[c] + w2 * a2[c];
+    } else {
+#pragma unroll
+        for (int c = 0; c < CV; c++) ga[c] = 0.0f;
+    }
+#pragma unroll
+    for (int c = 0; c < CV; c++) gbuf[i * CV + c] = ga[c];
+    float smp[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (TEX) {
+        float q[2] = {0.0f, 0.0f};
+        if (tri_corners(sc.uv_tris, sc.T, sc.Vuv, t, v0, v1, v2)) {
+            const float *u0 = sc.uv + 2 * (int64_t)v0, *u1 = sc.uv + 2 * (int64_t)v1, *u2 = sc.uv + 2 * (int64_t)v2;
+#pragma unroll
+            for (int c = 0; c < 2; c++) q[c] = w.x * u0[c] + w.y * u1[c] + w2 * u2[c];
+        }
+        uvbuf[2 * i] = q[0];
+        uvbuf[2 * i + 1] = q[1];
+        const Taps tp = make_taps(sc.td, q, 0);
+        if (tp.ok) tex_bilinear<4>(sc.tex, sc.td, tp, smp, 4);
+        reinterpret_cast<float4 *>(samp)[i] = make_float4(smp[0], smp[1], smp[2], smp[3]);
+    }
+    dressi_frag_in in{};
+    in.normal = ga;
+    in.pos = ga + 3;
+    in.albedo = TEX ? smp : ga + 6;
+    in.albedo_channels = TEX ? 4 : 3;
+    ShadeState s;
+    shade_forward(mode, in, sc.eye + 3 * (i / npix), 0, mode != DRESSI_SHADE_LAMBERT, s);
+    shade_color(mode, s, color + 3 * i);
+    sil[i] = 1.0f;
+}
+
+template <int CV, bool TEX>
+__global__ void __launch_bounds__(256)
+    k_packed_bwd(int mode, dressi_packed_scene sc, const int32_t *__restrict__ tri_id, int64_t npix, int64_t n,
+                 const float *__restrict__ gbuf, const float *__restrict__ uvbuf, const float *__restrict__ samp,
+                 const float *__restrict__ color, const float *__restrict__ sil, const float4 *__restrict__ target,
+                 float w, float *__restrict__ grad_color, float *__restrict__ grad_sil, float *__restrict__ g_gbuf,
+                 float *__restrict__ g_samp, float2 *__restrict__ g_bary_uv, int32_t *__restrict__ inv,
+                 float *__restrict__ partial, int skip_empty) {
+    __shared__ float red[256];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    float acc = 0.0f;
+    if (i < n) {
+        // L2 loss term and its gradient (the loss stage's arithmetic)
+        const float4 tg = target[i];
+        const float d0 = color[3 * i] - tg.x, d1 = color[3 * i + 1] - tg.y, d2 = color[3 * i + 2] - tg.z;
+        const float d3_ = sil[i] - tg.w;
+        acc += d0 * d0 + d1 * d1 + d2 * d2 + d3_ * d3_;
+        const float g0 = 2.0f * w * d0, g1 = 2.0f * w * d1, g2 = 2.0f * w * d2;
+        if (grad_color) {
+            grad_color[3 * i] = g0; grad_color[3 * i + 1] = g1; grad_color[3 * i + 2] = g2;
+        }
+        if (grad_sil) grad_sil[i] = 2.0f * w * d3_;
+        const int t = tri_id[i];
+        if (t < 0) {
+            if (!skip_empty) {
+#pragma unroll
+                for (int c = 0; c < CV; c++) g_gbuf[i * CV + c] = 0.0f;
+                if (TEX) {
+                    reinterpret_cast<float4 *>(g_samp)[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                    g_bary_uv[i] = make_float2(0.0f, 0.0f);
+                }
+            }
+        } else {
+            // the hard blend passes the colour gradient to the front layer unchanged
+            dressi_frag_in in{};
+            in.normal = gbuf; in.normal_stride = CV;
+            in.pos = gbuf + 3; in.pos_stride = CV;
+            in.albedo = TEX ? samp : gbuf + 6;
+            in.albedo_stride = TEX ? 4 : CV;
+            in.albedo_channels = TEX ? 4 : 3;
+            ShadeState s;
+            shade_forward(mode, in, sc.eye + 3 * (i / npix), i, mode != DRESSI_SHADE_LAMBERT, s);
+            dressi_frag_grad gr{};
+            gr.normal = g_gbuf; gr.normal_stride = CV;
+            gr.pos = g_gbuf + 3; gr.pos_stride = CV;
+            gr.albedo = TEX ? g_samp : g_gbuf + 6;
+            gr.albedo_stride = TEX ? 4 : CV;
+            shade_bwd_frag(mode, in, s, d3{g0, g1, g2}, nullptr, gr, i, true);
+            if (TEX) {
+                const float q[2] = {uvbuf[2 * i], uvbuf[2 * i + 1]};
+                const Taps tp = make_taps(sc.td, q, 0);
+                float du = 0.0f, dv = 0.0f;
+                if (tp.ok) {
+                    if (inv) {
+                        const int cx = cell1d(q[0], sc.td.Wt, sc.td.wrap_u);
+                        const int cy = cell1d(q[1], sc.td.Ht, sc.td.wrap_v);
+                        const int64_t sl = i / npix;
+                        atomicMax(&inv[sl * sc.td.Ht * sc.td.Wt + (int64_t)cy * sc.td.Wt + cx], (int)(i - sl * npix));
+                    }
+                    float gs[4];
+                    ldv<4>(g_samp + 4 * i, gs, 4);
+                    tex_dcoord<4>(sc.tex, sc.td, tp, gs, 4, du, dv);
+                }
+                // barycentric adjoint of the interpolated coordinate
+                float2 gb = make_float2(0.0f, 0.0f);
+                int v0, v1, v2;
+                if (tri_corners(sc.uv_tris, sc.T, sc.Vuv, t, v0, v1, v2)) {
+                    const float *u0 = sc.uv + 2 * (int64_t)v0, *u1 = sc.uv + 2 * (int64_t)v1,
+                                *u2 = sc.uv + 2 * (int64_t)v2;
+                    const float gq[2] = {du, dv};
+                    float a = 0.0f, b = 0.0f;
+#pragma unroll
+                    for (int c = 0; c < 2; c++) {
+                        a += gq[c] * (u0[c] - u2[c]);
+                        b += gq[c] * (u1[c] - u2[c]);
+                    }
+                    gb = make_float2(0.0f + a, 0.0f + b);
+                }
+                g_bary_uv[i] = gb;
+            }
+        }
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+static bool al16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+
+static int check_packed(dressi_ctx *ctx, const dressi_packed_scene *sc, int B, int H, int W, const char *what) {
+    if (!ctx) return DRESSI_EINVAL;
+    std::string w(what);
+    if (!sc || B < 0 || H < 0 || W < 0 || sc->V < 0 || sc->T < 0) return dressi_fail(ctx, DRESSI_EINVAL, w + ": bad arguments");
+    if (sc->mode == DRESSI_SHADE_LAMBERT) {
+        if (sc->Cv != 9) return dressi_fail(ctx, DRESSI_EINVAL, w + ": Lambert takes 9 attribute channels");
+    } else if (sc->mode == DRESSI_SHADE_PHONG) {
+        if (sc->Cv != 6) return dressi_fail(ctx, DRESSI_EINVAL, w + ": Phong takes 6 attribute channels");
+        if (!sc->uv || !sc->uv_tris || !sc->tex || sc->Vuv < 0)
+            return dressi_fail(ctx, DRESSI_EINVAL, w + ": Phong needs uv, uv_tris and the albedo texture");
+        if (sc->td.kind != DRESSI_TEX_2D || sc->td.Ct != 4 || sc->td.Ht < 1 || sc->td.Wt < 1 || !al16(sc->tex))
+            return dressi_fail(ctx, DRESSI_EINVAL, w + ": the albedo must be a 16-byte aligned 2-D RGBA texture");
+        if (sc->td.wrap_u < DRESSI_WRAP_REPEAT || sc->td.wrap_u > DRESSI_WRAP_CLAMP ||
+            sc->td.wrap_v < DRESSI_WRAP_REPEAT || sc->td.wrap_v > DRESSI_WRAP_CLAMP)
+            return dressi_fail(ctx, DRESSI_EINVAL, w + ": bad wrap mode");
+    } else {
+        return dressi_fail(ctx, DRESSI_EINVAL, w + ": mode must be Lambert or Phong");
+    }
+    if ((int64_t)B * H * W > 0 && (!sc->vattr || !sc->tris || !sc->eye))
+        return dressi_fail(ctx, DRESSI_EINVAL, w + ": null vattr, tris or eye");
+    return DRESSI_OK;
+}
+
+extern "C" int dressi_packed_forward(dressi_ctx *ctx, const dressi_packed_scene *sc, const int32_t *tri_id,
+                                     const float *bary, int B, int H, int W, float *gbuf, float *uvbuf,
+                                     float *samp, float *color, float *sil, uint8_t *edge, int32_t *inv,
+                                     void *stream) {
+    int rc = check_packed(ctx, sc, B, H, W, "packed_forward");
+    if (rc) return rc;
+    const int64_t npix = (int64_t)H * W, n = (int64_t)B * npix;
+    const bool tex = sc->mode == DRESSI_SHADE_PHONG;
+    if (inv && !tex) return dressi_fail(ctx, DRESSI_EINVAL, "packed_forward: inv is for the textured (Phong) pass");
+    if (inv && !al16(inv)) return dressi_fail(ctx, DRESSI_EINVAL, "packed_forward: inv must be 16-byte aligned");
+    if (n == 0) return DRESSI_OK;
+    if (!tri_id || !bary || !gbuf || !color || !sil || !edge || (tex && (!uvbuf || !samp)))
+        return dressi_fail(ctx, DRESSI_EINVAL, "packed_forward: null input or output");
+    if (tex && !al16(samp)) return dressi_fail(ctx, DRESSI_EINVAL, "packed_forward: samp must be 16-byte aligned");
+    const int64_t ncells = inv ? n / npix * (int64_t)sc->td.Ht * sc->td.Wt : 0;
+    hipStream_t st = (hipStream_t)stream;
+    const int g = (int)((n + 255) / 256);
+    const float2 *b2 = reinterpret_cast<const float2 *>(bary);
+    if (tex)
+        DR_LAUNCH("k_packed_fwd", (k_packed_fwd<6, true>), g, 256, 0, st, sc->mode, *sc, tri_id, b2, npix, n, gbuf,
+                  uvbuf, samp, color, sil, edge, inv, ncells, ctx->skip_empty);
+    else
+        DR_LAUNCH("k_packed_fwd", (k_packed_fwd<9, false>), g, 256, 0, st, sc->mode, *sc, tri_id, b2, npix, n, gbuf,
+                  uvbuf, samp, color, sil, edge, inv, ncells, ctx->skip_empty);
+    return dressi_launch_check(ctx, "packed_forward");
+}
+
+extern "C" int dressi_packed_backward(dressi_ctx *ctx, const dressi_packed_scene *sc, const int32_t *tri_id,
+                                      int B, int H, int W, const float *gbuf, const float *uvbuf,
+                                      const float *samp, const float *color, const float *sil,
+                                      const float *target, float *loss, float *grad_color, float *grad_sil,
+                                      float *grad_gbuf, float *grad_samp, float *grad_bary_uv, int32_t *inv,
+                                      void *stream) {
+    int rc = check_packed(ctx, sc, B, H, W, "packed_backward");
+    if (rc) return rc;
+    const int64_t npix = (int64_t)H * W, n = (int64_t)B * npix;
+    const bool tex = sc->mode == DRESSI_SHADE_PHONG;
+    if (!loss) return dressi_fail(ctx, DRESSI_EINVAL, "packed_backward: null loss");
+    if (inv && !tex) return dressi_fail(ctx, DRESSI_EINVAL, "packed_backward: inv is for the textured (Phong) pass");
+    if (n > 0 && (!tri_id || !gbuf || !color || !sil || !target || !grad_gbuf ||
+                  (tex && (!uvbuf || !samp || !grad_samp || !grad_bary_uv))))
+        return dressi_fail(ctx, DRESSI_EINVAL, "packed_backward: null input or output");
+    if (n > 0 && (!al16(target) || (tex && (!al16(samp) || !al16(grad_samp)))))
+        return dressi_fail(ctx, DRESSI_EINVAL, "packed_backward: target, samp and grad_samp must be 16-byte aligned");
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t nb = n > 0 ? (n + 255) / 256 : 1;
+    Carver c;
+    const size_t o_p = c.take(sizeof(float) * (size_t)nb);
+    if ((rc = dressi_scratch(ctx, c.off, st))) return rc;
+    float *partial = at<float>(ctx->scratch, o_p);
+    const float w = 1.0f / (4.0f * (float)(n > 0 ? n : 1));
+    const float4 *t4 = reinterpret_cast<const float4 *>(target);
+    float2 *gb = reinterpret_cast<float2 *>(grad_bary_uv);
+    if (n == 0) {
+        dressi_fill_f32(partial, 0.0f, 1, st);
+    } else if (tex) {
+        DR_LAUNCH("k_packed_bwd", (k_packed_bwd<6, true>), (int)nb, 256, 0, st, sc->mode, *sc, tri_id, npix, n, gbuf,
+                  uvbuf, samp, color, sil, t4, w, grad_color, grad_sil, grad_gbuf, grad_samp, gb, inv, partial,
+                  ctx->skip_empty);
+    } else {
+        DR_LAUNCH("k_packed_bwd", (k_packed_bwd<9, false>), (int)nb, 256, 0, st, sc->mode, *sc, tri_id, npix, n,
+                  gbuf, uvbuf, samp, color, sil, t4, w, grad_color, grad_sil, grad_gbuf, grad_samp, gb, inv, partial,
+                  ctx->skip_empty);
+    }
+    DR_LAUNCH("k_loss_sum", (k_loss_sum), 1, LOSS_BS, 0, st, partial, (int)nb, w, loss);
+    return dressi_launch_check(ctx, "packed_backward");
 }

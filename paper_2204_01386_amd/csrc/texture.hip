@@ -8,142 +8,8 @@
 // loop is the largest index).  Then one lane per texel gathers the kept
 // pixels of the distinct in-range cells of its 3x3 neighbourhood in every
 // slice, in a fixed order.  No float atomics.
-#include "dressi_internal.h"
+#include "texcore.h"
 
-struct Taps {
-    int ok;
-    int face;
-    int x0, x1, y0, y1;
-    float fx, fy;
-};
-
-// s = u*n - 1/2 (float), taps floor(s) + {0,1}, wrapped or clamped
-__device__ __forceinline__ void taps1d(float u, int n, int wrap, int &a, int &b, float &f) {
-    float s = u * (float)n;
-    s = s - 0.5f;
-    float fl = floorf(s);
-    f = s - fl;
-    a = (int)fl;
-    b = a + 1;
-    if (wrap == DRESSI_WRAP_REPEAT) {
-        a %= n;
-        if (a < 0) a += n;
-        b %= n;
-        if (b < 0) b += n;
-    } else {
-        a = min(max(a, 0), n - 1);
-        b = min(max(b, 0), n - 1);
-    }
-}
-
-__device__ __forceinline__ int cell1d(float u, int n, int wrap) {
-    float p = u * (float)n;
-    int c = (int)floorf(p);
-    if (wrap == DRESSI_WRAP_REPEAT) {
-        c %= n;
-        if (c < 0) c += n;
-    } else {
-        c = min(max(c, 0), n - 1);
-    }
-    return c;
-}
-
-// major-axis cube mapping (faces +X,-X,+Y,-Y,+Z,-Z; ties prefer x then y)
-__device__ __forceinline__ int cube_face(float x, float y, float z, float &u, float &v, float &sc,
-                                         float &tc, float &ma) {
-    float ax = fabsf(x), ay = fabsf(y), az = fabsf(z);
-    int f;
-    if (ax >= ay && ax >= az) {
-        ma = ax;
-        if (x >= 0.0f) { f = 0; sc = -z; tc = -y; }
-        else { f = 1; sc = z; tc = -y; }
-    } else if (ay >= az) {
-        ma = ay;
-        if (y >= 0.0f) { f = 2; sc = x; tc = z; }
-        else { f = 3; sc = x; tc = -z; }
-    } else {
-        ma = az;
-        if (z >= 0.0f) { f = 4; sc = x; tc = -y; }
-        else { f = 5; sc = -x; tc = -y; }
-    }
-    if (!(ma > 0.0f)) return -1;
-    float us = sc / ma, vs = tc / ma;
-    u = (us + 1.0f) * 0.5f;
-    v = (vs + 1.0f) * 0.5f;
-    return f;
-}
-
-// Number of 2-D faces or layers of a texture.
-__host__ __device__ __forceinline__ int tex_faces(const dressi_tex_desc &td) {
-    return td.kind == DRESSI_TEX_CUBE ? 6 : (td.kind == DRESSI_TEX_2D_ARRAY ? td.layers : 1);
-}
-
-// Layer of fragment i of a texture array (its triangle's layer), 0 otherwise.
-__device__ __forceinline__ int tex_layer(const dressi_tex_desc &td, const int32_t *__restrict__ tri_id,
-                                         int64_t i) {
-    return td.kind == DRESSI_TEX_2D_ARRAY ? td.tri_layer[tri_id[i]] : 0;
-}
-
-__device__ __forceinline__ Taps make_taps(const dressi_tex_desc &td, const float *q, int layer = 0) {
-    Taps t;
-    t.ok = 0;
-    float u, v;
-    int wu = td.wrap_u, wv = td.wrap_v;
-    t.face = 0;
-    if (td.kind == DRESSI_TEX_CUBE) {
-        float sc, tc, ma;
-        int f = cube_face(q[0], q[1], q[2], u, v, sc, tc, ma);
-        if (f < 0) return t;
-        t.face = f;
-        wu = wv = DRESSI_WRAP_CLAMP;
-    } else {
-        u = q[0];
-        v = q[1];
-        t.face = layer;
-    }
-    taps1d(u, td.Wt, wu, t.x0, t.x1, t.fx);
-    taps1d(v, td.Ht, wv, t.y0, t.y1, t.fy);
-    t.ok = 1;
-    return t;
-}
-
-// CT channels per texel or pixel (CT = 0: Ct at run time, at most 16).
-// Multiples of 4 are moved as float4 (16-byte aligned rows).
-template <int CT>
-__device__ __forceinline__ void ldv(const float *__restrict__ p, float *v, int Ct) {
-    if constexpr (CT > 0 && CT % 4 == 0) {
-#pragma unroll
-        for (int q = 0; q < CT / 4; q++) {
-            const float4 a = reinterpret_cast<const float4 *>(p)[q];
-            v[4 * q] = a.x; v[4 * q + 1] = a.y; v[4 * q + 2] = a.z; v[4 * q + 3] = a.w;
-        }
-    } else if constexpr (CT > 0) {
-#pragma unroll
-        for (int c = 0; c < CT; c++) v[c] = p[c];
-    } else {
-#pragma unroll
-        for (int c = 0; c < 16; c++)
-            if (c < Ct) v[c] = p[c];
-    }
-}
-
-template <int CT>
-__device__ __forceinline__ void stv(float *__restrict__ p, const float *v, int Ct) {
-    if constexpr (CT > 0 && CT % 4 == 0) {
-#pragma unroll
-        for (int q = 0; q < CT / 4; q++)
-            reinterpret_cast<float4 *>(p)[q] = make_float4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
-    } else if constexpr (CT > 0) {
-#pragma unroll
-        for (int c = 0; c < CT; c++) p[c] = v[c];
-    } else {
-#pragma unroll
-        for (int c = 0; c < 16; c++)
-            if (c < Ct) p[c] = v[c];
-    }
-}
-
-#define TEX_NC(CT) ((CT) > 0 ? (CT) : 16)
 
 template <int CT>
 __global__ void __launch_bounds__(256)
@@ -165,16 +31,7 @@ __global__ void __launch_bounds__(256)
         stv<CT>(y, r, Ct);
         return;
     }
-    const int64_t face = (int64_t)t.face * td.Ht * td.Wt;
-    float a[TEX_NC(CT)], b[TEX_NC(CT)], c4[TEX_NC(CT)], d[TEX_NC(CT)];
-    ldv<CT>(tex + (face + (int64_t)t.y0 * td.Wt + t.x0) * Ct, a, Ct);
-    ldv<CT>(tex + (face + (int64_t)t.y0 * td.Wt + t.x1) * Ct, b, Ct);
-    ldv<CT>(tex + (face + (int64_t)t.y1 * td.Wt + t.x0) * Ct, c4, Ct);
-    ldv<CT>(tex + (face + (int64_t)t.y1 * td.Wt + t.x1) * Ct, d, Ct);
-    const float w00 = (1.0f - t.fy) * (1.0f - t.fx), w01 = (1.0f - t.fy) * t.fx;
-    const float w10 = t.fy * (1.0f - t.fx), w11 = t.fy * t.fx;
-#pragma unroll
-    for (int c = 0; c < TEX_NC(CT); c++) r[c] = w00 * a[c] + w01 * b[c] + w10 * c4[c] + w11 * d[c];
+    tex_bilinear<CT>(tex, td, t, r, Ct);
     stv<CT>(y, r, Ct);
 }
 
@@ -218,22 +75,10 @@ __global__ void __launch_bounds__(256)
         for (int j = 0; j < cd; j++) gc[j] = 0.0f;
         return;
     }
-    const int64_t face = (int64_t)t.face * td.Ht * td.Wt;
-    float p00[TEX_NC(CT)], p01[TEX_NC(CT)], p10[TEX_NC(CT)], p11[TEX_NC(CT)], g[TEX_NC(CT)];
-    ldv<CT>(tex + (face + (int64_t)t.y0 * td.Wt + t.x0) * Ct, p00, Ct);
-    ldv<CT>(tex + (face + (int64_t)t.y0 * td.Wt + t.x1) * Ct, p01, Ct);
-    ldv<CT>(tex + (face + (int64_t)t.y1 * td.Wt + t.x0) * Ct, p10, Ct);
-    ldv<CT>(tex + (face + (int64_t)t.y1 * td.Wt + t.x1) * Ct, p11, Ct);
+    float g[TEX_NC(CT)];
     ldv<CT>(grad_out + i * Ct, g, Ct);
-    float du = 0.0f, dv = 0.0f;
-#pragma unroll
-    for (int c = 0; c < TEX_NC(CT); c++) {
-        if (CT == 0 && c >= Ct) break;
-        du += g[c] * ((1.0f - t.fy) * (p01[c] - p00[c]) + t.fy * (p11[c] - p10[c]));
-        dv += g[c] * ((1.0f - t.fx) * (p10[c] - p00[c]) + t.fx * (p11[c] - p01[c]));
-    }
-    du *= (float)td.Wt;
-    dv *= (float)td.Ht;
+    float du, dv;
+    tex_dcoord<CT>(tex, td, t, g, Ct, du, dv);
     if (!cube) {
         gc[0] = du;
         gc[1] = dv;
@@ -360,44 +205,46 @@ static Jitter jitter_of_frame(uint32_t frame) {
     return j;
 }
 
-// Texture gradient through the inverse UV.  One block of texels (16 columns,
-// 32 rows when one slice is staged at a time, else 16) per workgroup: per slice the cells
-// around the block (a one-cell halo) are staged in LDS
-// (wrapped, or -1 outside a clamped texture); blocks whose cells are all
-// empty skip the slice.  Each texel then visits its 3x3 cells in row-major
-// order and adds the kept pixel's gradient times that pixel's bilinear
-// weight on the texel.
+// Texture gradient through the inverse UV.  A workgroup of 256 lanes (16
+// columns x 16 rows) owns a block of 16 x 16R texels, R texels per lane (rows
+// ly, ly + 16, ...).  Per slice the cells around the block (a one-cell halo)
+// are staged in LDS (wrapped, or empty outside a clamped texture), each with
+// its winner's taps, bilinear fractions and gradient; blocks whose cells are
+// all empty skip the slice.  Each texel then visits its 3x3 cells in
+// row-major order and adds the kept pixel's gradient times that pixel's
+// bilinear weight on the texel.
 #define IV_T 16
 // Per texel: the sum over slices [s0, s1), in ascending order, of the distinct
 // in-range cells of its 3x3 block, row-major, of the winner pixel's bilinear
 // weight on this texel times its gradient.  A block of texels loads the
-// haloed cells of SG slices at once (all loads in flight), skips the
-// group when every cell is empty, then gathers.  With nsplit > 1 the slice
-// range is split over grid.z and each part writes its own partial sum.  SG
-// slices (DRESSI_IV_SG) are staged at a time, with each winner's taps and
-// gradient, so the texel loop reads LDS only.  A
-// winner found in a cell of face or layer f has its taps on f, so they are
-// recomputed from its coordinate alone.
-template <int SG>
+// haloed cells of SG slices at once (all loads in flight) and the next group's
+// while it works on the current one, skips a group when every cell is empty,
+// then gathers.  With nsplit > 1 the slice range is split over grid.z and each
+// part writes its own partial sum.  A winner found in a cell of face or layer
+// f has its taps on f, so they are recomputed from its coordinate alone.
+// More rows per lane (R) means fewer, larger blocks: more loads in flight per
+// lane and fewer halo cells per texel, against more LDS per block.
+template <int SG, int R>
 struct IvGeom {
-    static constexpr int TY = SG == 1 ? 32 : 16;   // texel rows per block (16 columns)
-    static constexpr int NT = IV_T * TY;           // threads
+    static constexpr int NT = 256;                 // lanes: 16 columns x 16 rows
+    static constexpr int TY = 16 * R;              // texel rows per block
     static constexpr int HW = IV_T + 2, HH = TY + 2, HN = HW * HH;   // halo
+    static constexpr int PT = (HN + NT - 1) / NT;  // halo cells per lane
 };
 
-template <int CT, int SG>
-__global__ void __launch_bounds__(IvGeom<SG>::NT) __attribute__((amdgpu_waves_per_eu(CT == 8 ? 8 : 1)))
+template <int CT, int SG, int R>
+__global__ void __launch_bounds__(256)
     k_invuv_gather(dressi_tex_desc td, const float *__restrict__ coord, const int32_t *__restrict__ tri_id,
                    int64_t npix, int S, int nsplit, const int32_t *__restrict__ inv,
                    const float *__restrict__ grad_out, float *__restrict__ out) {
-    // per halo cell of each slice of the group: the winner pixel (-1: none or
-    // another cube face), its four tap coordinates and bilinear fractions
-    using G = IvGeom<SG>;
-    __shared__ int cpix[SG][G::HN];
+    // per halo cell of each slice of the group: the winner's four tap
+    // coordinates, bilinear fractions (fx < 0: no winner, or one on another
+    // cube face) and pixel gradient
+    using G = IvGeom<SG, R>;
+    constexpr int NC = TEX_NC(CT);
     __shared__ int2 ctap[SG][G::HN];   // x0 | x1 << 16, y0 | y1 << 16
     __shared__ float2 cfr[SG][G::HN];  // fx, fy
-    // the winners' pixel gradients are staged as well
-    __shared__ float cg[SG][G::HN * TEX_NC(CT)];
+    __shared__ float cg[SG][G::HN * NC];
     const int Ht = td.Ht, Wt = td.Wt, Ct = CT > 0 ? CT : td.Ct;
     const bool cube = td.kind == DRESSI_TEX_CUBE;
     const int F = tex_faces(td);
@@ -409,15 +256,13 @@ __global__ void __launch_bounds__(IvGeom<SG>::NT) __attribute__((amdgpu_waves_pe
     const int s0 = part * per, s1 = min(S, s0 + per);
     const int bx0 = blockIdx.x * IV_T, by0 = blockIdx.y * G::TY;
     const int lx = threadIdx.x % IV_T, ly = threadIdx.x / IV_T;
-    const int tx = bx0 + lx, ty = by0 + ly;
-    const bool mine = tx < Wt && ty < Ht;
+    const int tx = bx0 + lx;
     const int64_t face_cells = (int64_t)Ht * Wt;
     const int64_t cells_all = (int64_t)F * face_cells;
-    // this thread's halo entries (row-major over the halo) and their cell offsets
-    static_assert(G::HN <= 2 * G::NT, "two halo cells per thread");
-    int hoff[2];
+    // this lane's halo entries (row-major over the halo) and their cell offsets
+    int hoff[G::PT];
 #pragma unroll
-    for (int k = 0; k < 2; k++) {
+    for (int k = 0; k < G::PT; k++) {
         const int h = threadIdx.x + k * G::NT;
         hoff[k] = -1;
         if (h < G::HN) {
@@ -430,76 +275,76 @@ __global__ void __launch_bounds__(IvGeom<SG>::NT) __attribute__((amdgpu_waves_pe
             if (ok) hoff[k] = cy * Wt + cx;
         }
     }
-    float acc[TEX_NC(CT)];
+    float acc[R][NC];
 #pragma unroll
-    for (int c = 0; c < TEX_NC(CT); c++) acc[c] = 0.0f;
+    for (int r = 0; r < R; r++)
+#pragma unroll
+        for (int c = 0; c < NC; c++) acc[r][c] = 0.0f;
     // winners of a group's halo cells; the next group's are loaded while the
     // current one is processed
-    auto load_group = [&](int g0, int (*w)[2]) {
+    auto load_group = [&](int g0, int (*w)[G::PT]) {
         const int ng = min(SG, s1 - g0);
 #pragma unroll
         for (int q = 0; q < SG; q++) {
             const int32_t *iv = inv + (int64_t)(g0 + q) * cells_all + (int64_t)f * face_cells;
 #pragma unroll
-            for (int k = 0; k < 2; k++) w[q][k] = (q < ng && hoff[k] >= 0) ? iv[hoff[k]] : -1;
+            for (int k = 0; k < G::PT; k++) w[q][k] = (q < ng && hoff[k] >= 0) ? iv[hoff[k]] : -1;
         }
     };
-    int wnext[SG][2];
+    int wnext[SG][G::PT];
     if (s0 < s1) load_group(s0, wnext);
     for (int g0 = s0; g0 < s1; g0 += SG) {
         const int ng = min(SG, s1 - g0);
-        int wpix[SG][2];
+        int wpix[SG][G::PT];
 #pragma unroll
-        for (int q = 0; q < SG; q++) {
-            wpix[q][0] = wnext[q][0];
-            wpix[q][1] = wnext[q][1];
-        }
+        for (int q = 0; q < SG; q++)
+#pragma unroll
+            for (int k = 0; k < G::PT; k++) wpix[q][k] = wnext[q][k];
         if (g0 + SG < s1) load_group(g0 + SG, wnext);
         int found = 0;
         // each winner's taps, computed once for the up to 9 texels that visit it
 #pragma unroll
         for (int q = 0; q < SG; q++) {
 #pragma unroll
-            for (int k = 0; k < 2; k++) {
+            for (int k = 0; k < G::PT; k++) {
                 const int h = threadIdx.x + k * G::NT;
                 if (h >= G::HN) continue;
-                int i = wpix[q][k];
+                const int i = wpix[q][k];
                 int2 tp = make_int2(0, 0);
-                float2 fr = make_float2(0.0f, 0.0f);
+                float2 fr = make_float2(-1.0f, 0.0f);
                 if (i >= 0) {
                     const int64_t o = (int64_t)(g0 + q) * npix + i;
                     // the winner's gradient is read alongside its coordinate
-                    float g[TEX_NC(CT)];
+                    float g[NC];
                     ldv<CT>(grad_out + o * Ct, g, Ct);
                     const Taps t = make_taps(td, coord + o * cd, f);
-                    if (!t.ok || t.face != f) {
-                        i = -1;
-                    } else {
+                    if (t.ok && t.face == f) {
                         tp = make_int2(t.x0 | (t.x1 << 16), t.y0 | (t.y1 << 16));
                         fr = make_float2(t.fx, t.fy);
+                        found = 1;
 #pragma unroll
-                        for (int c = 0; c < TEX_NC(CT); c++)
-                            if (CT > 0 || c < Ct) cg[q][h * TEX_NC(CT) + c] = g[c];
+                        for (int c = 0; c < NC; c++)
+                            if (CT > 0 || c < Ct) cg[q][h * NC + c] = g[c];
                     }
                 }
-                cpix[q][h] = i;
                 ctap[q][h] = tp;
                 cfr[q][h] = fr;
-                found |= i >= 0;
             }
         }
         if (!__syncthreads_or(found)) continue;
-        if (mine) {
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+            const int ry = ly + 16 * r, ty = by0 + ry;
+            if (tx >= Wt || ty >= Ht) continue;
             for (int q = 0; q < ng; q++) {
 #pragma unroll
                 for (int dy = 0; dy < 3; dy++) {
 #pragma unroll
                     for (int dx = 0; dx < 3; dx++) {
-                        const int h = (ly + dy) * G::HW + lx + dx;
-                        const int i = cpix[q][h];
-                        if (i < 0) continue;
-                        const int2 tp = ctap[q][h];
+                        const int h = (ry + dy) * G::HW + lx + dx;
                         const float2 fr = cfr[q][h];
+                        if (fr.x < 0.0f) continue;
+                        const int2 tp = ctap[q][h];
                         const int x0 = tp.x & 0xffff, x1 = tp.x >> 16, y0 = tp.y & 0xffff, y1 = tp.y >> 16;
                         float w = 0.0f;
                         if (y0 == ty && x0 == tx) w += (1.0f - fr.y) * (1.0f - fr.x);
@@ -507,22 +352,26 @@ __global__ void __launch_bounds__(IvGeom<SG>::NT) __attribute__((amdgpu_waves_pe
                         if (y1 == ty && x0 == tx) w += fr.y * (1.0f - fr.x);
                         if (y1 == ty && x1 == tx) w += fr.y * fr.x;
                         if (w == 0.0f) continue;
-                        float g[TEX_NC(CT)];
+                        float g[NC];
 #pragma unroll
-                        for (int c = 0; c < TEX_NC(CT); c++)
-                            if (CT > 0 || c < Ct) g[c] = cg[q][h * TEX_NC(CT) + c];
+                        for (int c = 0; c < NC; c++)
+                            if (CT > 0 || c < Ct) g[c] = cg[q][h * NC + c];
 #pragma unroll
-                        for (int c = 0; c < TEX_NC(CT); c++)
-                            if (CT > 0 || c < Ct) acc[c] += w * g[c];
+                        for (int c = 0; c < NC; c++)
+                            if (CT > 0 || c < Ct) acc[r][c] += w * g[c];
                     }
                 }
             }
         }
         __syncthreads();
     }
-    if (!mine) return;
-    float *gt = out + ((int64_t)part * cells_all + (int64_t)f * face_cells + (int64_t)ty * Wt + tx) * Ct;
-    stv<CT>(gt, acc, Ct);
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        const int ty = by0 + ly + 16 * r;
+        if (tx >= Wt || ty >= Ht) continue;
+        float *gt = out + ((int64_t)part * cells_all + (int64_t)f * face_cells + (int64_t)ty * Wt + tx) * Ct;
+        stv<CT>(gt, acc[r], Ct);
+    }
 }
 
 // Sums the per-part partial texture gradients in part order.
@@ -534,23 +383,46 @@ __global__ void k_invuv_reduce(const float *__restrict__ part, int nsplit, int64
     out[i] = a;
 }
 
-template <int SG>
-static void launch_gather(int ct, dim3 g, hipStream_t st, const dressi_tex_desc &td, const float *coord,
-                          const int32_t *tri_id, int64_t npix, int S, int nsplit, const int32_t *inv,
-                          const float *grad_out, float *dst) {
-    constexpr int nt = IvGeom<SG>::NT;
+template <int SG, int R>
+static void launch_gather_r(int ct, dim3 g, hipStream_t st, const dressi_tex_desc &td, const float *coord,
+                            const int32_t *tri_id, int64_t npix, int S, int nsplit, const int32_t *inv,
+                            const float *grad_out, float *dst) {
+    constexpr int nt = IvGeom<SG, R>::NT;
     if (ct == 4)
-        DR_LAUNCH("k_invuv_gather", (k_invuv_gather<4, SG>), g, nt, 0, st, td, coord, tri_id, npix, S,
+        DR_LAUNCH("k_invuv_gather", (k_invuv_gather<4, SG, R>), g, nt, 0, st, td, coord, tri_id, npix, S,
                   nsplit, inv, grad_out, dst);
     else if (ct == 3)
-        DR_LAUNCH("k_invuv_gather", (k_invuv_gather<3, SG>), g, nt, 0, st, td, coord, tri_id, npix, S,
+        DR_LAUNCH("k_invuv_gather", (k_invuv_gather<3, SG, R>), g, nt, 0, st, td, coord, tri_id, npix, S,
                   nsplit, inv, grad_out, dst);
     else if (ct == 8)
-        DR_LAUNCH("k_invuv_gather", (k_invuv_gather<8, SG>), g, nt, 0, st, td, coord, tri_id, npix, S,
+        DR_LAUNCH("k_invuv_gather", (k_invuv_gather<8, SG, R>), g, nt, 0, st, td, coord, tri_id, npix, S,
                   nsplit, inv, grad_out, dst);
     else
-        DR_LAUNCH("k_invuv_gather", (k_invuv_gather<0, SG>), g, nt, 0, st, td, coord, tri_id, npix, S,
+        DR_LAUNCH("k_invuv_gather", (k_invuv_gather<0, SG, 1>), g, nt, 0, st, td, coord, tri_id, npix, S,
                   nsplit, inv, grad_out, dst);
+}
+
+// Texel rows per lane of the gather: `rows` (1, 2 or 4) or, for 0, 2 rows
+// for a single slice and 1 for several (measured: with one slice the larger
+// blocks are faster, with many the loop over slices prefers more, smaller
+// blocks in flight).  Any choice gives the same sums in the same order.
+static int gather_rows(int rows, int ct, int S) {
+    if (ct != 3 && ct != 4 && ct != 8) return 1;
+    if (rows == 1 || rows == 2 || rows == 4) return rows;
+    return S == 1 ? 2 : 1;
+}
+
+static void launch_gather(int rows, int ct, int64_t gx, int64_t ty_cells, int gz, hipStream_t st,
+                          const dressi_tex_desc &td, const float *coord, const int32_t *tri_id, int64_t npix,
+                          int S, int nsplit, const int32_t *inv, const float *grad_out, float *dst) {
+    const int R = gather_rows(rows, ct, S);
+    dim3 g((unsigned)gx, (unsigned)((ty_cells + 16 * R - 1) / (16 * R)), (unsigned)gz);
+    if (R == 4)
+        launch_gather_r<DRESSI_IV_SG, 4>(ct, g, st, td, coord, tri_id, npix, S, nsplit, inv, grad_out, dst);
+    else if (R == 2)
+        launch_gather_r<DRESSI_IV_SG, 2>(ct, g, st, td, coord, tri_id, npix, S, nsplit, inv, grad_out, dst);
+    else
+        launch_gather_r<DRESSI_IV_SG, 1>(ct, g, st, td, coord, tri_id, npix, S, nsplit, inv, grad_out, dst);
 }
 
 // float4 rows need 16-byte aligned bases
@@ -628,15 +500,13 @@ static void tex_bwd_pixels(const float *tex, const dressi_tex_desc &td, const fl
 // grid as well and the parts summed afterwards in `part`.
 static void tex_gather(const dressi_tex_desc &td, const float *coord, const int32_t *tri_id, int64_t npix,
                        int S, const int32_t *inv, const float *grad_out, float *part, float *grad_tex,
-                       hipStream_t st) {
+                       hipStream_t st, int rows) {
     const int64_t cells = (int64_t)tex_faces(td) * td.Ht * td.Wt;
     const int nsplit = dressi_invuv_nsplit(cells, S);
     float *dst = nsplit > 1 ? part : grad_tex;
-    const int ty = IvGeom<DRESSI_IV_SG>::TY;
-    dim3 g((unsigned)((td.Wt + IV_T - 1) / IV_T), (unsigned)((td.Ht + ty - 1) / ty),
-           (unsigned)(tex_faces(td) * nsplit));
     const int ct = aligned16(grad_out, dst) ? td.Ct : 0;
-    launch_gather<DRESSI_IV_SG>(ct, g, st, td, coord, tri_id, npix, S, nsplit, inv, grad_out, dst);
+    launch_gather(rows, ct, (td.Wt + IV_T - 1) / IV_T, td.Ht, tex_faces(td) * nsplit, st, td, coord, tri_id,
+                  npix, S, nsplit, inv, grad_out, dst);
     if (nsplit > 1) {
         int64_t ne = cells * td.Ct;
         DR_LAUNCH("k_invuv_reduce", (k_invuv_reduce), (int)((ne + 255) / 256), 256, 0, st, part, nsplit, ne,
@@ -687,7 +557,7 @@ extern "C" int dressi_texture_bwd(dressi_ctx *ctx, const float *tex, const dress
     }
     if (!jit) {
         tex_bwd_pixels(tex, *td, coord, tri_id, npix, S, grad_out, grad_coord, inv, st, ctx->skip_empty);
-        if (grad_tex) tex_gather(*td, coord, tri_id, npix, S, inv, grad_out, part, grad_tex, st);
+        if (grad_tex) tex_gather(*td, coord, tri_id, npix, S, inv, grad_out, part, grad_tex, st, ctx->iv_rows);
         return dressi_launch_check(ctx, "texture_bwd");
     }
     // jittered registration beside the unmoved coordinate gradient
@@ -707,7 +577,7 @@ extern "C" int dressi_texture_bwd(dressi_ctx *ctx, const float *tex, const dress
                            grad_out, j, jc, jg, inv); break;
         }
     }
-    tex_gather(*td, jc, tri_id, npix, S, inv, jg, part, grad_tex, st);
+    tex_gather(*td, jc, tri_id, npix, S, inv, jg, part, grad_tex, st, ctx->iv_rows);
     return dressi_launch_check(ctx, "texture_bwd");
 }
 
@@ -745,7 +615,7 @@ extern "C" int dressi_texture_grad_invuv(dressi_ctx *ctx, const dressi_tex_desc 
         if ((rc = dressi_scratch(ctx, pb, st))) return rc;
         part = at<float>(ctx->scratch, 0);
     }
-    tex_gather(*td, coord, tri_id, (int64_t)H * W, S, inv, grad_out, part, grad_tex, st);
+    tex_gather(*td, coord, tri_id, (int64_t)H * W, S, inv, grad_out, part, grad_tex, st, ctx->iv_rows);
     return dressi_launch_check(ctx, "texture_grad_invuv");
 }
 

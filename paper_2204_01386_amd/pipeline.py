@@ -257,6 +257,24 @@ class Step(_TwoStreams):
         self.frag_index = torch.empty(nbytes, dtype=torch.uint8, device=dev)
         self._fin = self._frag_in()
         self._fin_dir = self._frag_in(with_env=False)
+        # stage packing (§3.3.3) of the single-layer hard image: interpolation,
+        # texture, shading and blend as one forward pass, the loss and their
+        # adjoints as one backward pass (same values; the loss is summed in
+        # other groups); scene.extra["packed"] = False keeps the separate stages
+        self.packed = (K == 1 and self.blend == Bd.BLEND_HARD and bool(scene.extra.get("packed", True))
+                       and (self.mode == Bd.SHADE_LAMBERT
+                            or (self.mode == Bd.SHADE_PHONG and self.Ct == 4 and self.desc.kind == Bd.TEX_2D)))
+        self.inv = None
+        if self.packed:
+            ps = Bd.PackedScene()
+            ps.mode, ps.vattr, ps.V, ps.Cv = self.mode, _p(self.vattr), self.V, self.Cv
+            ps.tris, ps.T, ps.eye = _p(self.tris), self.T, _p(self.eye)
+            if self.mode == Bd.SHADE_PHONG:
+                ps.uv, ps.uv_tris, ps.Vuv = _p(self.uv), _p(self.uv_tris), self.uv.shape[0]
+                ps.tex, ps.td = _p(self.tex), self.desc
+                nb = int(_lib.dressi_invuv_bytes(C.byref(self.desc), B))
+                self.inv = torch.empty(nb // 4, dtype=torch.int32, device=dev)
+            self._pscene = ps
         self.hard_raster = None     # rasterization strategy chosen by autotune() (None: triangle-parallel)
         self.hybrid_weight = HYBRID_WEIGHT_DEFAULT
         self._calibrate_bins()
@@ -334,6 +352,12 @@ class Step(_TwoStreams):
         self._fork("index")
         self._chk2(_lib.dressi_fragment_index(self._h2("index"), _p(self.tri_id), B, K, H, W, T, _p(self.frag_index),
                                               self._sa("index")), "fragment_index", "index")
+        if self.packed:
+            ck(_lib.dressi_packed_forward(h, C.byref(self._pscene), _p(self.tri_id), _p(self.bary), B, H, W,
+                                          _p(self.gbuf), _p(self.uvbuf), _p(self.samp), _p(self.color),
+                                          _p(self.sil), _p(self.E), _p(self.inv), s), "packed_forward")
+            self._join()
+            return
         ck(_lib.dressi_interpolate(h, _p(self.vattr), 1, V, self.Cv, _p(self.tris), T, _p(self.tri_id),
                                    _p(self.bary), B, K, H, W, _p(self.gbuf), s), "interpolate")
         if self.uv is not None:
@@ -401,6 +425,40 @@ class Step(_TwoStreams):
                                            None, _p(self.frag_index), _p(self.uv_adj), None,
                                            _p(self.g_bary_uv), s), "interpolate_bwd uv")
             gb_in = self.g_bary_uv
+        self._backward_geometry(gb_in)
+        self._join()
+
+    def _packed_backward(self):
+        """Loss, blend, shading and texture-coordinate adjoints in one pass
+        (with the inverse-UV registration), then the texture gather and the
+        geometry's backward as in the separate form."""
+        h, s = self.ctx.handle, self._s()
+        B, H, W, K = self.B, self.H, self.W, self.K
+        ck = self._chk
+        ck(_lib.dressi_packed_backward(h, C.byref(self._pscene), _p(self.tri_id), B, H, W, _p(self.gbuf),
+                                       _p(self.uvbuf), _p(self.samp), _p(self.color), _p(self.sil),
+                                       _p(self.target), _p(self.loss), None, None, _p(self.g_gbuf),
+                                       _p(self.g_samp), _p(self.g_bary_uv), _p(self.inv), s), "packed_backward")
+        gb_in = None
+        if self.uv is not None:
+            # the texel gather beside the geometry's backward ("texel" branch)
+            self._fork("texel")
+            self._chk2(_lib.dressi_texture_grad_invuv(self._h2("texel"), C.byref(self.desc), _p(self.uvbuf),
+                                                      _p(self.tri_id), B * K, H, W, _p(self.inv), _p(self.g_samp),
+                                                      _p(self.g_tex), self._sa("texel")),
+                       "texture_grad_invuv", "texel")
+            gb_in = self.g_bary_uv
+        self._backward_geometry(gb_in)
+        self._join()
+
+    def _backward_geometry(self, gb_in):
+        """Attribute interpolation, rasterization, transform and vertex
+        attribute adjoints, from the G-buffer gradient (and the barycentric
+        gradient gb_in of the texture coordinates)."""
+        h, s = self.ctx.handle, self._s()
+        B, V, T, H, W, K = self.B, self.V, self.T, self.H, self.W, self.K
+        ck = self._chk
+        Cv = self.Cv
         ck(_lib.dressi_interpolate_bwd(h, _p(self.vattr), 1, V, Cv, _p(self.tris), T, _p(self.tri_id),
                                        _p(self.bary), B, K, H, W, _p(self.g_gbuf), _p(gb_in),
                                        _p(self.frag_index), _p(self.adj), _p(self.g_vattr),
@@ -414,11 +472,16 @@ class Step(_TwoStreams):
         ck(_lib.dressi_vertex_attrs_bwd(h, _p(self.pos), _p(self.tris), V, T, Cv, _p(self.adj),
                                         _p(self.g_vattr), _p(self.g_pos_t), _p(self.g_pos), s),
            "vertex_attrs_bwd")
-        self._join()
 
     def run(self):
-        """One full step: forward, loss and gradient, backward."""
+        """One full step: forward, loss and gradient, backward.  In the packed
+        form (and without inverse-UV jitter) the loss and the backward are one
+        pass, which leaves g_color and g_sil unwritten."""
         self.forward()
+        if self.packed and self.frame == 0:
+            with self._sparse():
+                self._packed_backward()
+            return
         self.loss_and_grad()
         self.backward()
 

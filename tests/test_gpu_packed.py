@@ -1,0 +1,178 @@
+"""The packed single-layer pass (stage packing, §3.3.3: the per-fragment
+stages of one image size in one pass) against the separate stages it packs:
+for single-layer hard rendering (K = 1, hard blend) with Lambert or textured
+Phong shading, the packed forward and backward give bitwise the image, every
+intermediate that leaves the pass and every gradient of the separate form,
+and the loss to float rounding (its partial sums are grouped differently).
+Also eager against graph replays, an empty image, and the entry points'
+argument checks."""
+import ctypes as C
+
+import numpy as np
+import pytest
+import torch
+
+from test_gpu_parity import host
+from test_gpu_step import _compare_step
+from paper_2204_01386_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def Bd():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2204_01386_amd import binding
+    return binding
+
+
+def _ragged_two_views(seed=2):
+    """Config-2 style textured Phong scene, two cameras, 97 x 131 pixels
+    (neither a multiple of a tile nor of a block), 96^2 texture."""
+    s = scenes.config2(seed, H=97, subdiv=4, tex_size=96)
+    s.W = 131
+    eyes = scenes.camera_ring(2, seed)
+    s.mvp, s.eyes = scenes.view_proj(eyes), eyes.astype(np.float32)
+    return s
+
+
+def _scene(which):
+    if which == "config1":
+        return scenes.config1()
+    if which == "config2":
+        return scenes.config2()
+    return _ragged_two_views()
+
+
+def _run(scene, packed, skip_empty=True):
+    from paper_2204_01386_amd.pipeline import Step, make_target
+    scene.extra["packed"] = packed
+    st = Step(scene, target=make_target(scene))
+    assert st.packed == packed
+    st.skip_empty = skip_empty
+    st.run()
+    torch.cuda.synchronize()
+    return st
+
+
+@pytest.mark.parametrize("which", ["config1", "config2", "ragged"])
+@pytest.mark.parametrize("skip_empty", [True, False])
+def test_packed_matches_separate_stages(Bd, which, skip_empty):
+    s = _scene(which)
+    a = _run(s, True, skip_empty)
+    b = _run(s, False, skip_empty)
+    cov = host(a.tri_id) >= 0
+    assert cov.any() and (~cov).any()
+    assert np.array_equal(host(a.tri_id), host(b.tri_id))
+    assert np.array_equal(host(a.rgba()), host(b.rgba())), "image differs"
+    assert np.array_equal(host(a.E), host(b.E))
+    La, Lb = float(host(a.loss)[0]), float(host(b.loss)[0])
+    assert abs(La - Lb) <= 1e-6 * Lb, (La, Lb)
+    # intermediates that leave the pass, at covered fragments
+    bufs = ["gbuf", "g_gbuf"] + (["uvbuf", "samp", "g_samp", "g_bary_uv"] if a.uv is not None else [])
+    for k in bufs:
+        x, y = host(getattr(a, k)), host(getattr(b, k))
+        assert np.array_equal(x[cov], y[cov]), f"{k} differs at covered fragments"
+        if not skip_empty:
+            assert np.array_equal(x[~cov], y[~cov]), f"{k} differs at empty fragments"
+    ga, gb = a.grads(), b.grads()
+    assert ga.keys() == gb.keys()
+    for k in ga:
+        assert np.array_equal(host(ga[k]), host(gb[k])), f"gradient {k} differs"
+    assert a.ctx.check_status() == 0
+
+
+def test_packed_two_ragged_views_against_the_oracle(Bd):
+    """The packed step on two views of a ragged image size, image and every
+    gradient against the oracle."""
+    st = _compare_step(_ragged_two_views())
+    assert st.packed
+
+
+@pytest.mark.parametrize("concurrent", [False, "texel", True])
+def test_packed_graph_replay(Bd, concurrent):
+    """Eager runs and graph replays of the packed step give the same bits,
+    also with the texel gather on the second stream."""
+    from paper_2204_01386_amd.pipeline import Step, make_target
+    s = _ragged_two_views(5)
+    st = Step(s, target=make_target(s))
+    assert st.packed
+    st.concurrent = concurrent
+    st.run()
+    torch.cuda.synchronize()
+    ref = {k: host(v).copy() for k, v in st.grads().items()}
+    ref_img, ref_loss = host(st.rgba()), host(st.loss).copy()
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        st.run()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g):
+        st.run()
+    for rep in range(3):
+        for v in list(st.grads().values()) + [st.color, st.sil, st.loss]:
+            v.fill_(7.0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(host(st.rgba()), ref_img), f"replay {rep}: image"
+        assert np.array_equal(host(st.loss), ref_loss), f"replay {rep}: loss"
+        for k, v in st.grads().items():
+            assert np.array_equal(host(v), ref[k]), f"replay {rep}: {k} differs from eager"
+        st.run()     # eager work between the replays
+        torch.cuda.synchronize()
+
+
+def test_packed_empty_image(Bd):
+    """A mesh outside the view frustum: nothing is covered, the image and
+    every gradient are zero and the loss is the mean square of the target."""
+    from paper_2204_01386_amd.pipeline import Step
+    s = scenes.config2(H=64, subdiv=3, tex_size=32)
+    s.pos = (s.pos + np.array([50.0, 0.0, 0.0], np.float32)).astype(np.float32)
+    st = Step(s)
+    assert st.packed
+    tgt = torch.rand_like(st.target)
+    st.target.copy_(tgt)
+    st.run()
+    torch.cuda.synchronize()
+    assert (host(st.tri_id) < 0).all()
+    assert not host(st.rgba()).any()
+    t = host(tgt).astype(np.float64)
+    assert abs(float(host(st.loss)[0]) - np.mean(t ** 2)) <= 1e-6 * np.mean(t ** 2)
+    for k, v in st.grads().items():
+        assert not host(v).any(), f"{k} gradient should be zero"
+
+
+def test_packed_entry_point_checks(Bd):
+    """Arguments the pass does not take are refused with DRESSI_EINVAL before
+    any launch: the environment-reflection mode, a wrong attribute width, a
+    texture that is not RGBA, an unaligned sample buffer, and an inverse-UV
+    map for the untextured pass."""
+    from paper_2204_01386_amd.pipeline import Step, _p
+    s = scenes.config2(H=32, subdiv=2, tex_size=16)
+    st = Step(s)
+    lib, h = Bd._lib, st.ctx.handle
+    base = st._pscene
+
+    def fwd(ps, samp=st.samp, inv=st.inv):
+        return lib.dressi_packed_forward(h, C.byref(ps), _p(st.tri_id), _p(st.bary), 1, st.H, st.W, _p(st.gbuf),
+                                         _p(st.uvbuf), _p(samp) if isinstance(samp, torch.Tensor) else samp,
+                                         _p(st.color), _p(st.sil), _p(st.E), _p(inv) if inv is not None else None,
+                                         Bd._stream())
+
+    def clone():
+        return Bd.PackedScene.from_buffer_copy(base)
+
+    assert fwd(base) == 0
+    ps = clone(); ps.mode = Bd.SHADE_PHONG_ENV
+    assert fwd(ps) == Bd.EINVAL
+    ps = clone(); ps.Cv = 9
+    assert fwd(ps) == Bd.EINVAL
+    ps = clone(); ps.td.Ct = 3
+    assert fwd(ps) == Bd.EINVAL
+    assert fwd(base, samp=st.samp.data_ptr() + 4) == Bd.EINVAL
+    ps = clone(); ps.mode = Bd.SHADE_LAMBERT; ps.Cv = 9
+    assert fwd(ps, inv=st.inv) == Bd.EINVAL
+    torch.cuda.synchronize()
