@@ -527,7 +527,9 @@ def _strategy_name(hr, w):
 
 
 def _tuned_json(t):
-    name = {False: "one stream", "index": "fragment index on a second stream", True: "two streams"}
+    name = {False: "one stream", "index": "fragment index on a second stream",
+            "texel": "texel gather on a second stream",
+            ("index", "texel"): "fragment index and texel gather on a second stream", True: "two streams"}
     return {"hard_raster": _strategy_name(t["hard_raster"], t["hybrid_weight"]),
             "raster_ms": {_strategy_name(*k): round(v, 4) for k, v in t["ms"].items()},
             "schedule": name[t["streams"]["concurrent"]],

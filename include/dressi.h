@@ -532,7 +532,9 @@ int dressi_packed_forward(dressi_ctx *ctx, const dressi_packed_scene *scene, con
  * fed to dressi_interpolate_bwd of uv), and, when inv is given (as set by
  * dressi_packed_forward), every covered pixel registered in it as
  * dressi_invuv_build does: dressi_texture_grad_invuv then gives the texture
- * gradient.  Inputs are the forward's outputs. */
+ * gradient.  Inputs are the forward's outputs.  Phong: grad_gbuf and
+ * grad_bary_uv may be NULL (only the albedo sample's gradient, as a
+ * texture-only step needs). */
 int dressi_packed_backward(dressi_ctx *ctx, const dressi_packed_scene *scene, const int32_t *tri_id, int B,
                            int H, int W, const float *gbuf, const float *uvbuf, const float *samp,
                            const float *color, const float *sil, const float *target, float *loss,

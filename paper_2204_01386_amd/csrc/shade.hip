@@ -857,11 +857,13 @@ __global__ void __launch_bounds__(256)
         const int t = tri_id[i];
         if (t < 0) {
             if (!skip_empty) {
+                if (g_gbuf) {
 #pragma unroll
-                for (int c = 0; c < CV; c++) g_gbuf[i * CV + c] = 0.0f;
+                    for (int c = 0; c < CV; c++) g_gbuf[i * CV + c] = 0.0f;
+                }
                 if (TEX) {
                     reinterpret_cast<float4 *>(g_samp)[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-                    g_bary_uv[i] = make_float2(0.0f, 0.0f);
+                    if (g_bary_uv) g_bary_uv[i] = make_float2(0.0f, 0.0f);
                 }
             }
         } else {
@@ -874,23 +876,26 @@ __global__ void __launch_bounds__(256)
             in.albedo_channels = TEX ? 4 : 3;
             ShadeState s;
             shade_forward(mode, in, sc.eye + 3 * (i / npix), i, mode != DRESSI_SHADE_LAMBERT, s);
+            // without g_gbuf only the albedo sample's gradient (texture-only steps)
             dressi_frag_grad gr{};
-            gr.normal = g_gbuf; gr.normal_stride = CV;
-            gr.pos = g_gbuf + 3; gr.pos_stride = CV;
-            gr.albedo = TEX ? g_samp : g_gbuf + 6;
+            if (g_gbuf) {
+                gr.normal = g_gbuf; gr.normal_stride = CV;
+                gr.pos = g_gbuf + 3; gr.pos_stride = CV;
+            }
+            gr.albedo = TEX ? g_samp : (g_gbuf ? g_gbuf + 6 : nullptr);
             gr.albedo_stride = TEX ? 4 : CV;
-            shade_bwd_frag(mode, in, s, d3{g0, g1, g2}, nullptr, gr, i, true);
-            if (TEX) {
+            shade_bwd_frag(mode, in, s, d3{g0, g1, g2}, nullptr, gr, i, g_gbuf != nullptr);
+            if (TEX && (inv || g_bary_uv)) {
                 const float q[2] = {uvbuf[2 * i], uvbuf[2 * i + 1]};
                 const Taps tp = make_taps(sc.td, q, 0);
                 float du = 0.0f, dv = 0.0f;
-                if (tp.ok) {
-                    if (inv) {
-                        const int cx = cell1d(q[0], sc.td.Wt, sc.td.wrap_u);
-                        const int cy = cell1d(q[1], sc.td.Ht, sc.td.wrap_v);
-                        const int64_t sl = i / npix;
-                        atomicMax(&inv[sl * sc.td.Ht * sc.td.Wt + (int64_t)cy * sc.td.Wt + cx], (int)(i - sl * npix));
-                    }
+                if (tp.ok && inv) {
+                    const int cx = cell1d(q[0], sc.td.Wt, sc.td.wrap_u);
+                    const int cy = cell1d(q[1], sc.td.Ht, sc.td.wrap_v);
+                    const int64_t sl = i / npix;
+                    atomicMax(&inv[sl * sc.td.Ht * sc.td.Wt + (int64_t)cy * sc.td.Wt + cx], (int)(i - sl * npix));
+                }
+                if (tp.ok && g_bary_uv) {
                     float gs[4];
                     ldv<4>(g_samp + 4 * i, gs, 4);
                     tex_dcoord<4>(sc.tex, sc.td, tp, gs, 4, du, dv);
@@ -910,7 +915,7 @@ __global__ void __launch_bounds__(256)
                     }
                     gb = make_float2(0.0f + a, 0.0f + b);
                 }
-                g_bary_uv[i] = gb;
+                if (g_bary_uv) g_bary_uv[i] = gb;
             }
         }
     }
@@ -962,7 +967,7 @@ extern "C" int dressi_packed_forward(dressi_ctx *ctx, const dressi_packed_scene 
     if (!tri_id || !bary || !gbuf || !color || !sil || !edge || (tex && (!uvbuf || !samp)))
         return dressi_fail(ctx, DRESSI_EINVAL, "packed_forward: null input or output");
     if (tex && !al16(samp)) return dressi_fail(ctx, DRESSI_EINVAL, "packed_forward: samp must be 16-byte aligned");
-    const int64_t ncells = inv ? n / npix * (int64_t)sc->td.Ht * sc->td.Wt : 0;
+    const int64_t ncells = inv ? (int64_t)B * sc->td.Ht * sc->td.Wt : 0;
     hipStream_t st = (hipStream_t)stream;
     const int g = (int)((n + 255) / 256);
     const float2 *b2 = reinterpret_cast<const float2 *>(bary);
@@ -987,8 +992,8 @@ extern "C" int dressi_packed_backward(dressi_ctx *ctx, const dressi_packed_scene
     const bool tex = sc->mode == DRESSI_SHADE_PHONG;
     if (!loss) return dressi_fail(ctx, DRESSI_EINVAL, "packed_backward: null loss");
     if (inv && !tex) return dressi_fail(ctx, DRESSI_EINVAL, "packed_backward: inv is for the textured (Phong) pass");
-    if (n > 0 && (!tri_id || !gbuf || !color || !sil || !target || !grad_gbuf ||
-                  (tex && (!uvbuf || !samp || !grad_samp || !grad_bary_uv))))
+    if (n > 0 && (!tri_id || !gbuf || !color || !sil || !target || (!tex && !grad_gbuf) ||
+                  (tex && (!uvbuf || !samp || !grad_samp))))
         return dressi_fail(ctx, DRESSI_EINVAL, "packed_backward: null input or output");
     if (n > 0 && (!al16(target) || (tex && (!al16(samp) || !al16(grad_samp)))))
         return dressi_fail(ctx, DRESSI_EINVAL, "packed_backward: target, samp and grad_samp must be 16-byte aligned");

@@ -56,7 +56,7 @@ class _TwoStreams:
     rasterization ("attrs"), the fragment index beside the rest of the
     forward ("index") and the texel gradients beside the coordinate
     gradients ("texel").  `concurrent` is False (every call on the caller's
-    stream), True (every branch) or the name of one branch.  Every fork makes
+    stream), True (every branch), the name of one branch or a tuple of names.  Every fork makes
     the second stream wait for the main one and every join the reverse, so a
     step stays one ordered unit on the caller's stream, also when it is
     captured into a graph.  Which is faster depends on the workload
@@ -99,7 +99,7 @@ class _TwoStreams:
 
     def _on(self, branch):
         c = self.concurrent
-        return c is True or (isinstance(c, str) and c == branch)
+        return c is True or (isinstance(c, str) and c == branch) or (isinstance(c, tuple) and branch in c)
 
     def _fork(self, branch):
         if self._on(branch):
@@ -554,6 +554,13 @@ class TextureStep:
         st = self.st
         h, s, ck = st.ctx.handle, st._s(), st._chk
         B, K, H, W = st.B, st.K, st.H, st.W
+        if getattr(st, "packed", False):
+            # the packed pass samples, shades and blends in one kernel (it
+            # recomputes the cheap interpolation beside them); the map stays
+            ck(_lib.dressi_packed_forward(h, C.byref(st._pscene), _p(st.tri_id), _p(st.bary), B, H, W,
+                                          _p(st.gbuf), _p(st.uvbuf), _p(st.samp), _p(st.color), _p(st.sil),
+                                          _p(st.E), None, s), "packed_forward")
+            return
         ck(_lib.dressi_texture(h, _p(st.tex), C.byref(st.desc), _p(st.uvbuf), _p(st.tri_id), B * K, H, W,
                                _p(st.samp), s), "texture")
         if st.env is not None:
@@ -599,8 +606,22 @@ class TextureStep:
         st._join()
 
     def run(self):
-        """One texture-only step: forward, loss and gradient, backward."""
+        """One texture-only step: forward, loss and gradient, backward (in the
+        packed form the loss and the albedo sample's adjoint are one pass, as
+        in the wrapped Step)."""
         self.forward()
+        st = self.st
+        if getattr(st, "packed", False):
+            h, s, ck = st.ctx.handle, st._s(), st._chk
+            with st._sparse():
+                ck(_lib.dressi_packed_backward(h, C.byref(st._pscene), _p(st.tri_id), st.B, st.H, st.W,
+                                               _p(st.gbuf), _p(st.uvbuf), _p(st.samp), _p(st.color), _p(st.sil),
+                                               _p(st.target), _p(st.loss), None, None, None, _p(st.g_samp),
+                                               None, None, s), "packed_backward")
+                ck(_lib.dressi_texture_grad_invuv(h, C.byref(st.desc), _p(st.uvbuf), _p(st.tri_id), st.B * st.K,
+                                                  st.H, st.W, _p(self.inv), _p(st.g_samp), _p(st.g_tex), s),
+                   "texture_grad_invuv")
+            return
         self.loss_and_grad()
         self.backward()
 
@@ -948,11 +969,11 @@ def autotune(step, reps: int = 5) -> dict:
 
 def autotune_streams(step, reps: int = 20) -> dict:
     """Chooses between issuing the whole step on the caller's stream, running
-    only the fragment index on a second stream, and running every independent
-    branch there, by timing graph replays of the captured step in each mode
-    (the results are the same)."""
+    the fragment index, the texel gather or both on a second stream, and
+    running every independent branch there, by timing graph replays of the
+    captured step in each mode (the results are the same)."""
     results = {}
-    for mode in (False, "index", True):
+    for mode in (False, "index", "texel", ("index", "texel"), True):
         step.concurrent = mode
         side = torch.cuda.Stream()
         side.wait_stream(torch.cuda.current_stream())

@@ -8,6 +8,7 @@ import numpy as np
 import pytest
 import torch
 
+import oracle
 from oracle import step as ostep
 from paper_2204_01386_amd import scenes
 from test_gpu_parity import assert_grad_close, dev, host
@@ -51,9 +52,13 @@ def test_invuv_split_matches_texture_bwd(B, case):
     ref2, _ = B.dressi_texture_bwd(dev(tex), dev(coord), dev(tid), dev(g2), need_coord=False, **kw)
     assert np.array_equal(host(B.dressi_texture_grad_invuv(dev(tex), dev(coord), dev(tid), inv, dev(g2), **kw)),
                           host(ref2))
+    # the map is the oracle's, bit-exact
+    F, Ht, Wt = (6, tex.shape[1], tex.shape[2]) if case == "cube" else (1, tex.shape[0], tex.shape[1])
+    cells = host(inv).reshape(S, F, Ht, Wt)
+    want = oracle.invuv_build(tex.shape, coord, tid, **kw)
+    assert np.array_equal(cells, want.reshape(S, F, Ht, Wt)), "inverse-UV cells differ from the oracle's"
     if case == "empty_slice":
-        F, Ht, Wt = 1, tex.shape[0], tex.shape[1]
-        assert (host(inv).reshape(S, F, Ht, Wt)[1] == -1).all()
+        assert (cells[1] == -1).all()
 
 
 def test_invuv_errors(B):
