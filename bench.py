@@ -172,6 +172,8 @@ class Shapes:
         self.S = st.B * st.K
         self.adj = (st.V + 1 + 3 * st.T) * 4
         self.uvadj = (self.Vuv + 1 + 3 * st.T) * 4
+        # the packed single-layer pass replaces the per-fragment stages
+        self.packed = bool(getattr(st, "packed", False))
 
     def touched(self, cells, C):
         return min(cells, 4 * self.cov) * C * 4
@@ -214,6 +216,23 @@ def call_bytes(z: Shapes):
         out["interpolate_bwd uv"] = z.Vuv * 8 + T * 12 + N * 4 + c * (8 + 8) + c * 8
         out["texture_bwd"] = (N * 4 + c * (8 + z.Ct * 4) + z.touched(z.cells, z.Ct) + c * 8
                               + z.S * z.cells * 4 * 2 + c * 4 + win * (8 + z.Ct * 4) + z.cells * z.Ct * 4)
+    if z.packed:
+        # interpolation, texture, shading, blend, loss and their adjoints as
+        # one forward and one backward pass: only what leaves the pass moves
+        for k in ("interpolate", "interpolate uv", "texture", "shade", "softras", "loss_l2", "softras_bwd",
+                  "shade_bwd", "texture_bwd", "interpolate_bwd uv"):
+            out.pop(k, None)
+        tex_in = (z.Vuv * 8 + T * 12 + z.touched(z.cells, z.Ct)) if z.Ct else 0
+        g_gbuf = Cv * 4 if z.mode == 0 else 24          # normal, position (, colour) gradients
+        out["packed_forward"] = (N * 4 + c * 8 + V * Cv * 4 + T * 12 + tex_in + B * 12
+                                 + c * Cv * 4 + (c * (8 + z.Ct * 4) + z.S * z.cells * 4 if z.Ct else 0)
+                                 + P * (12 + 4 + 1))
+        out["packed_backward"] = (N * 4 + c * Cv * 4 + (c * (8 + z.Ct * 4) + tex_in if z.Ct else 0)
+                                  + P * (12 + 4 + 16) + B * 12
+                                  + c * g_gbuf + (c * (z.Ct * 4 + 8 + 4) if z.Ct else 0))
+        if z.Ct:
+            win = min(c, z.S * z.cells)
+            out["texture_grad_invuv"] = z.S * z.cells * 4 + win * (8 + z.Ct * 4) + z.cells * z.Ct * 4
     if z.env:
         ewin = min(c, z.S * z.ecells)
         out["shade dir"] = N * 4 + c * (12 + 12 + 12 + 12) + B * 12 + c * 12
@@ -230,6 +249,9 @@ def kernel_bytes(name, z: Shapes):
     N, P, V, T, Cv, B, c = z.N, z.P, z.V, z.T, z.Cv, z.B, z.cov
     d = 4 if z.soft else 0
     cb = call_bytes(z)
+    if z.packed and name in ("k_interp", "k_tex_fwd", "k_shade", "k_shade_bwd", "k_blend", "k_blend_bwd",
+                             "k_loss_l2", "k_tex_bwd_pixel"):
+        return None
     if name in ("k_raster", "k_raster_list"):
         return cb["rasterize"] - B * V * 16 - T * 12
     if name == "k_setup_bin":
@@ -242,12 +264,16 @@ def kernel_bytes(name, z: Shapes):
         return z.S * z.cells * 4 + min(c, z.S * z.cells) * (8 + z.Ct * 4) + z.cells * z.Ct * 4
     if name == "k_tex_bwd_pixel" and not z.env:
         return N * 4 + c * (8 + z.Ct * 4) + z.touched(z.cells, z.Ct) + c * 8 + c * 4
+    if name == "k_packed_fwd":
+        return cb.get("packed_forward")
+    if name == "k_packed_bwd":
+        return cb.get("packed_backward")
     if name == "k_blend":
-        return cb["softras"]
+        return cb.get("softras")
     if name == "k_blend_bwd":
-        return cb["softras_bwd"]
+        return cb.get("softras_bwd")
     if name == "k_loss_l2":
-        return cb["loss_l2"]
+        return cb.get("loss_l2")
     if name == "k_interp_bwd_tile":
         return N * 4 + c * (8 + Cv * 4) + V * Cv * 4 + T * 12 + (c * 8 if z.Ct else 0) + c * 8
     if name == "k_interp_bwd_bary":

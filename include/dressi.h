@@ -493,7 +493,8 @@ int dressi_loss_l2(dressi_ctx *ctx, const float *color, const float *sil, const 
  * blend: the image is the front fragment's colour where one is present).
  * Shading: DRESSI_SHADE_LAMBERT with per-vertex normal, position and colour
  * (Cv = 9), or DRESSI_SHADE_PHONG with per-vertex normal and position (Cv = 6),
- * per-corner texture coordinates and a 2-D RGBA albedo texture.
+ * per-corner texture coordinates and a 2-D RGBA albedo texture (or a texture
+ * array, layer td.tri_layer[t] for triangle t: uneven batches).
  * ------------------------------------------------------------------------- */
 typedef struct {
     int mode;                 /* DRESSI_SHADE_LAMBERT or DRESSI_SHADE_PHONG */
@@ -504,9 +505,11 @@ typedef struct {
     const float *uv;          /* Phong: [Vuv, 2] texture coordinates, indexed by uv_tris [T, 3] */
     const int32_t *uv_tris;
     int Vuv;
-    const float *tex;         /* Phong: [Ht, Wt, 4] albedo (kind 2-D, Ct = 4), 16-byte aligned */
+    const float *tex;         /* Phong: [Ht, Wt, 4] albedo (kind 2-D, Ct = 4) or [layers, Ht, Wt, 4]
+                                 (kind 2-D array), 16-byte aligned */
     dressi_tex_desc td;
-    const float *eye;         /* [B, 3] camera positions */
+    const float *eye;         /* camera positions [B, 3], or [n, 3] with tri_eye */
+    const int32_t *tri_eye;   /* uneven batches: camera of each triangle, or NULL: eye[view] */
 } dressi_packed_scene;
 
 /* Forward of the packed pass over B views of H x W (tri_id [B,H,W] and bary
@@ -521,8 +524,8 @@ typedef struct {
 int dressi_packed_forward(dressi_ctx *ctx, const dressi_packed_scene *scene, const int32_t *tri_id,
                           const float *bary, int B, int H, int W, float *gbuf, float *uvbuf, float *samp,
                           float *color, float *sil, uint8_t *edge, int32_t *inv, void *stream);
-/* Backward of the packed pass with the L2 loss of dressi_loss_l2 (uniform
- * weight) against target [B,H,W,4]: loss [1] (its partial sums grouped by 256
+/* Backward of the packed pass with the L2 loss of dressi_loss_l2 against
+ * target [B,H,W,4] (weight [B,H,W] or NULL, as there): loss [1] (its partial sums grouped by 256
  * pixels, so it may differ from dressi_loss_l2's in the last bits);
  * grad_color, grad_sil (nullable) as dressi_loss_l2 writes them; grad_gbuf
  * [B,H,W,Cv] and, Phong, grad_samp [B,H,W,4] as dressi_softras_bwd and
@@ -537,9 +540,9 @@ int dressi_packed_forward(dressi_ctx *ctx, const dressi_packed_scene *scene, con
  * texture-only step needs). */
 int dressi_packed_backward(dressi_ctx *ctx, const dressi_packed_scene *scene, const int32_t *tri_id, int B,
                            int H, int W, const float *gbuf, const float *uvbuf, const float *samp,
-                           const float *color, const float *sil, const float *target, float *loss,
-                           float *grad_color, float *grad_sil, float *grad_gbuf, float *grad_samp,
-                           float *grad_bary_uv, int32_t *inv, void *stream);
+                           const float *color, const float *sil, const float *target, const float *weight,
+                           float *loss, float *grad_color, float *grad_sil, float *grad_gbuf,
+                           float *grad_samp, float *grad_bary_uv, int32_t *inv, void *stream);
 
 /* ----------------------------------------------------------------------------
  * The optimisation loop around the step (§4.1: vertex positions fitted to

@@ -55,7 +55,8 @@ class FragIn(C.Structure):
 class PackedScene(C.Structure):
     """dressi_packed_scene: the inputs of the packed single-layer pass."""
     _fields_ = [("mode", _i), ("vattr", _vp), ("V", _i), ("Cv", _i), ("tris", _vp), ("T", _i),
-                ("uv", _vp), ("uv_tris", _vp), ("Vuv", _i), ("tex", _vp), ("td", TexDesc), ("eye", _vp)]
+                ("uv", _vp), ("uv_tris", _vp), ("Vuv", _i), ("tex", _vp), ("td", TexDesc), ("eye", _vp),
+                ("tri_eye", _vp)]
 
 
 class FragGrad(C.Structure):
@@ -119,7 +120,7 @@ _SIG = {
     "dressi_loss_l2": [_vp, _vp, _vp, _vp, _vp, _i, _i, _i, _vp, _vp, _vp, _vp],
     "dressi_packed_forward": [_vp, _vp, _vp, _vp, _i, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
     "dressi_packed_backward": [_vp, _vp, _vp, _i, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
-                               _vp, _vp, _vp, _vp],
+                               _vp, _vp, _vp, _vp, _vp],
     "dressi_transform_batched": [_vp, _vp, _vp, _vp, _i, _vp, _vp],
     "dressi_tune": [_vp, _i, _i64],
     "dressi_transform_batched_bwd": [_vp, _vp, _vp, _i, _vp, _vp, _vp],

@@ -676,7 +676,15 @@ __global__ void __launch_bounds__(LOSS_BS)
     k_loss_sum(const float *__restrict__ partial, int nb, float scale, float *__restrict__ loss) {
     __shared__ float red[LOSS_BS];
     float a = 0.0f;
-    for (int i = threadIdx.x; i < nb; i += LOSS_BS) a += partial[i];
+    // the partials i, i + LOSS_BS, ... in order; eight loads in flight
+    for (int i = threadIdx.x; i < nb; i += 8 * LOSS_BS) {
+        float v[8];
+#pragma unroll
+        for (int j = 0; j < 8; j++) v[j] = i + j * LOSS_BS < nb ? partial[i + j * LOSS_BS] : 0.0f;
+#pragma unroll
+        for (int j = 0; j < 8; j++)
+            if (i + j * LOSS_BS < nb) a += v[j];
+    }
     red[threadIdx.x] = a;
     __syncthreads();
     for (int s = LOSS_BS / 2; s > 0; s >>= 1) {
@@ -731,9 +739,10 @@ size_t dr_need_shade(const dressi_limits &l) {
     c.take(dressi_adjacency_tmp_bytes(std::max(l.V, 0), std::max(l.T, 0)));
     c.take(sizeof(float) * 3 * (size_t)std::max(l.V, 0));
     // the loss partials: LOSS_MAX_BLOCKS (dressi_loss_l2) or one per 256
-    // pixels (dressi_packed_backward)
+    // pixels, at most 65536 (dressi_packed_backward)
     const size_t pix = (size_t)std::max(l.B, 0) * std::max(l.H, 0) * std::max(l.W, 0);
-    return std::max({c.off, sizeof(float) * (size_t)LOSS_MAX_BLOCKS, sizeof(float) * ((pix + 255) / 256)});
+    return std::max({c.off, sizeof(float) * (size_t)LOSS_MAX_BLOCKS,
+                     sizeof(float) * std::min<size_t>((pix + 255) / 256, 65536)});
 }
 
 // ---------------------------------------------------------------------------
@@ -817,7 +826,7 @@ __global__ void __launch_bounds__(256)
         }
         uvbuf[2 * i] = q[0];
         uvbuf[2 * i + 1] = q[1];
-        const Taps tp = make_taps(sc.td, q, 0);
+        const Taps tp = make_taps(sc.td, q, tex_layer(sc.td, tri_id, i));
         if (tp.ok) tex_bilinear<4>(sc.tex, sc.td, tp, smp, 4);
         reinterpret_cast<float4 *>(samp)[i] = make_float4(smp[0], smp[1], smp[2], smp[3]);
     }
@@ -826,8 +835,9 @@ __global__ void __launch_bounds__(256)
     in.pos = ga + 3;
     in.albedo = TEX ? smp : ga + 6;
     in.albedo_channels = TEX ? 4 : 3;
+    const int64_t e = sc.tri_eye ? (int64_t)sc.tri_eye[t] : i / npix;
     ShadeState s;
-    shade_forward(mode, in, sc.eye + 3 * (i / npix), 0, mode != DRESSI_SHADE_LAMBERT, s);
+    shade_forward(mode, in, sc.eye + 3 * e, 0, mode != DRESSI_SHADE_LAMBERT, s);
     shade_color(mode, s, color + 3 * i);
     sil[i] = 1.0f;
 }
@@ -837,18 +847,24 @@ __global__ void __launch_bounds__(256)
     k_packed_bwd(int mode, dressi_packed_scene sc, const int32_t *__restrict__ tri_id, int64_t npix, int64_t n,
                  const float *__restrict__ gbuf, const float *__restrict__ uvbuf, const float *__restrict__ samp,
                  const float *__restrict__ color, const float *__restrict__ sil, const float4 *__restrict__ target,
-                 float w, float *__restrict__ grad_color, float *__restrict__ grad_sil, float *__restrict__ g_gbuf,
-                 float *__restrict__ g_samp, float2 *__restrict__ g_bary_uv, int32_t *__restrict__ inv,
-                 float *__restrict__ partial, int skip_empty) {
+                 const float *__restrict__ weight, float w_uniform, float *__restrict__ grad_color,
+                 float *__restrict__ grad_sil, float *__restrict__ g_gbuf, float *__restrict__ g_samp,
+                 float2 *__restrict__ g_bary_uv, int32_t *__restrict__ inv, float *__restrict__ partial,
+                 int skip_empty) {
     __shared__ float red[256];
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     float acc = 0.0f;
-    if (i < n) {
+    // one pixel per lane (grid-stride when the image has more pixels than the
+    // grid has lanes: each lane's loss terms are added in pixel order)
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
         // L2 loss term and its gradient (the loss stage's arithmetic)
         const float4 tg = target[i];
         const float d0 = color[3 * i] - tg.x, d1 = color[3 * i + 1] - tg.y, d2 = color[3 * i + 2] - tg.z;
         const float d3_ = sil[i] - tg.w;
-        acc += d0 * d0 + d1 * d1 + d2 * d2 + d3_ * d3_;
+        const float sq = d0 * d0 + d1 * d1 + d2 * d2 + d3_ * d3_;
+        // per-pixel weight (uneven batches), else uniform
+        const float w = weight ? weight[i] : w_uniform;
+        acc += weight ? w * sq : sq;
         const float g0 = 2.0f * w * d0, g1 = 2.0f * w * d1, g2 = 2.0f * w * d2;
         if (grad_color) {
             grad_color[3 * i] = g0; grad_color[3 * i + 1] = g1; grad_color[3 * i + 2] = g2;
@@ -874,8 +890,9 @@ __global__ void __launch_bounds__(256)
             in.albedo = TEX ? samp : gbuf + 6;
             in.albedo_stride = TEX ? 4 : CV;
             in.albedo_channels = TEX ? 4 : 3;
+            const int64_t e = sc.tri_eye ? (int64_t)sc.tri_eye[t] : i / npix;
             ShadeState s;
-            shade_forward(mode, in, sc.eye + 3 * (i / npix), i, mode != DRESSI_SHADE_LAMBERT, s);
+            shade_forward(mode, in, sc.eye + 3 * e, i, mode != DRESSI_SHADE_LAMBERT, s);
             // without g_gbuf only the albedo sample's gradient (texture-only steps)
             dressi_frag_grad gr{};
             if (g_gbuf) {
@@ -887,13 +904,15 @@ __global__ void __launch_bounds__(256)
             shade_bwd_frag(mode, in, s, d3{g0, g1, g2}, nullptr, gr, i, g_gbuf != nullptr);
             if (TEX && (inv || g_bary_uv)) {
                 const float q[2] = {uvbuf[2 * i], uvbuf[2 * i + 1]};
-                const Taps tp = make_taps(sc.td, q, 0);
+                const Taps tp = make_taps(sc.td, q, tex_layer(sc.td, tri_id, i));
                 float du = 0.0f, dv = 0.0f;
                 if (tp.ok && inv) {
                     const int cx = cell1d(q[0], sc.td.Wt, sc.td.wrap_u);
                     const int cy = cell1d(q[1], sc.td.Ht, sc.td.wrap_v);
                     const int64_t sl = i / npix;
-                    atomicMax(&inv[sl * sc.td.Ht * sc.td.Wt + (int64_t)cy * sc.td.Wt + cx], (int)(i - sl * npix));
+                    const int64_t cells = (int64_t)tex_faces(sc.td) * sc.td.Ht * sc.td.Wt;
+                    atomicMax(&inv[sl * cells + ((int64_t)tp.face * sc.td.Ht + cy) * sc.td.Wt + cx],
+                              (int)(i - sl * npix));
                 }
                 if (tp.ok && g_bary_uv) {
                     float gs[4];
@@ -925,10 +944,13 @@ __global__ void __launch_bounds__(256)
         if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
         __syncthreads();
     }
+    // a second launch adds the partials: an agent-scope fence per workgroup
+    // (for a last-workgroup sum) writes back the XCD's L2 and costs far more
     if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
 static bool al16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+#define PACKED_MAX_BLOCKS 65536   // loss partials of the packed backward, at most
 
 static int check_packed(dressi_ctx *ctx, const dressi_packed_scene *sc, int B, int H, int W, const char *what) {
     if (!ctx) return DRESSI_EINVAL;
@@ -940,8 +962,12 @@ static int check_packed(dressi_ctx *ctx, const dressi_packed_scene *sc, int B, i
         if (sc->Cv != 6) return dressi_fail(ctx, DRESSI_EINVAL, w + ": Phong takes 6 attribute channels");
         if (!sc->uv || !sc->uv_tris || !sc->tex || sc->Vuv < 0)
             return dressi_fail(ctx, DRESSI_EINVAL, w + ": Phong needs uv, uv_tris and the albedo texture");
-        if (sc->td.kind != DRESSI_TEX_2D || sc->td.Ct != 4 || sc->td.Ht < 1 || sc->td.Wt < 1 || !al16(sc->tex))
-            return dressi_fail(ctx, DRESSI_EINVAL, w + ": the albedo must be a 16-byte aligned 2-D RGBA texture");
+        if ((sc->td.kind != DRESSI_TEX_2D && sc->td.kind != DRESSI_TEX_2D_ARRAY) || sc->td.Ct != 4 ||
+            sc->td.Ht < 1 || sc->td.Wt < 1 || !al16(sc->tex))
+            return dressi_fail(ctx, DRESSI_EINVAL,
+                               w + ": the albedo must be a 16-byte aligned 2-D RGBA texture or texture array");
+        if (sc->td.kind == DRESSI_TEX_2D_ARRAY && (sc->td.layers < 1 || !sc->td.tri_layer))
+            return dressi_fail(ctx, DRESSI_EINVAL, w + ": a texture array needs layers and tri_layer");
         if (sc->td.wrap_u < DRESSI_WRAP_REPEAT || sc->td.wrap_u > DRESSI_WRAP_CLAMP ||
             sc->td.wrap_v < DRESSI_WRAP_REPEAT || sc->td.wrap_v > DRESSI_WRAP_CLAMP)
             return dressi_fail(ctx, DRESSI_EINVAL, w + ": bad wrap mode");
@@ -967,7 +993,7 @@ extern "C" int dressi_packed_forward(dressi_ctx *ctx, const dressi_packed_scene 
     if (!tri_id || !bary || !gbuf || !color || !sil || !edge || (tex && (!uvbuf || !samp)))
         return dressi_fail(ctx, DRESSI_EINVAL, "packed_forward: null input or output");
     if (tex && !al16(samp)) return dressi_fail(ctx, DRESSI_EINVAL, "packed_forward: samp must be 16-byte aligned");
-    const int64_t ncells = inv ? (int64_t)B * sc->td.Ht * sc->td.Wt : 0;
+    const int64_t ncells = inv ? (int64_t)B * tex_faces(sc->td) * sc->td.Ht * sc->td.Wt : 0;
     hipStream_t st = (hipStream_t)stream;
     const int g = (int)((n + 255) / 256);
     const float2 *b2 = reinterpret_cast<const float2 *>(bary);
@@ -983,9 +1009,9 @@ extern "C" int dressi_packed_forward(dressi_ctx *ctx, const dressi_packed_scene 
 extern "C" int dressi_packed_backward(dressi_ctx *ctx, const dressi_packed_scene *sc, const int32_t *tri_id,
                                       int B, int H, int W, const float *gbuf, const float *uvbuf,
                                       const float *samp, const float *color, const float *sil,
-                                      const float *target, float *loss, float *grad_color, float *grad_sil,
-                                      float *grad_gbuf, float *grad_samp, float *grad_bary_uv, int32_t *inv,
-                                      void *stream) {
+                                      const float *target, const float *weight, float *loss, float *grad_color,
+                                      float *grad_sil, float *grad_gbuf, float *grad_samp, float *grad_bary_uv,
+                                      int32_t *inv, void *stream) {
     int rc = check_packed(ctx, sc, B, H, W, "packed_backward");
     if (rc) return rc;
     const int64_t npix = (int64_t)H * W, n = (int64_t)B * npix;
@@ -998,7 +1024,7 @@ extern "C" int dressi_packed_backward(dressi_ctx *ctx, const dressi_packed_scene
     if (n > 0 && (!al16(target) || (tex && (!al16(samp) || !al16(grad_samp)))))
         return dressi_fail(ctx, DRESSI_EINVAL, "packed_backward: target, samp and grad_samp must be 16-byte aligned");
     hipStream_t st = (hipStream_t)stream;
-    const int64_t nb = n > 0 ? (n + 255) / 256 : 1;
+    const int64_t nb = n > 0 ? std::min<int64_t>((n + 255) / 256, PACKED_MAX_BLOCKS) : 1;
     Carver c;
     const size_t o_p = c.take(sizeof(float) * (size_t)nb);
     if ((rc = dressi_scratch(ctx, c.off, st))) return rc;
@@ -1010,13 +1036,13 @@ extern "C" int dressi_packed_backward(dressi_ctx *ctx, const dressi_packed_scene
         dressi_fill_f32(partial, 0.0f, 1, st);
     } else if (tex) {
         DR_LAUNCH("k_packed_bwd", (k_packed_bwd<6, true>), (int)nb, 256, 0, st, sc->mode, *sc, tri_id, npix, n, gbuf,
-                  uvbuf, samp, color, sil, t4, w, grad_color, grad_sil, grad_gbuf, grad_samp, gb, inv, partial,
+                  uvbuf, samp, color, sil, t4, weight, w, grad_color, grad_sil, grad_gbuf, grad_samp, gb, inv, partial,
                   ctx->skip_empty);
     } else {
         DR_LAUNCH("k_packed_bwd", (k_packed_bwd<9, false>), (int)nb, 256, 0, st, sc->mode, *sc, tri_id, npix, n,
-                  gbuf, uvbuf, samp, color, sil, t4, w, grad_color, grad_sil, grad_gbuf, grad_samp, gb, inv, partial,
+                  gbuf, uvbuf, samp, color, sil, t4, weight, w, grad_color, grad_sil, grad_gbuf, grad_samp, gb, inv, partial,
                   ctx->skip_empty);
     }
-    DR_LAUNCH("k_loss_sum", (k_loss_sum), 1, LOSS_BS, 0, st, partial, (int)nb, w, loss);
+    DR_LAUNCH("k_loss_sum", (k_loss_sum), 1, LOSS_BS, 0, st, partial, (int)nb, weight ? 1.0f : w, loss);
     return dressi_launch_check(ctx, "packed_backward");
 }

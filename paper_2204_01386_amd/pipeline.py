@@ -437,7 +437,7 @@ class Step(_TwoStreams):
         ck = self._chk
         ck(_lib.dressi_packed_backward(h, C.byref(self._pscene), _p(self.tri_id), B, H, W, _p(self.gbuf),
                                        _p(self.uvbuf), _p(self.samp), _p(self.color), _p(self.sil),
-                                       _p(self.target), _p(self.loss), None, None, _p(self.g_gbuf),
+                                       _p(self.target), None, _p(self.loss), None, None, _p(self.g_gbuf),
                                        _p(self.g_samp), _p(self.g_bary_uv), _p(self.inv), s), "packed_backward")
         gb_in = None
         if self.uv is not None:
@@ -616,8 +616,8 @@ class TextureStep:
             with st._sparse():
                 ck(_lib.dressi_packed_backward(h, C.byref(st._pscene), _p(st.tri_id), st.B, st.H, st.W,
                                                _p(st.gbuf), _p(st.uvbuf), _p(st.samp), _p(st.color), _p(st.sil),
-                                               _p(st.target), _p(st.loss), None, None, None, _p(st.g_samp),
-                                               None, None, s), "packed_backward")
+                                               _p(st.target), _p(getattr(st, "weight", None)), _p(st.loss), None,
+                                               None, None, _p(st.g_samp), None, None, s), "packed_backward")
                 ck(_lib.dressi_texture_grad_invuv(h, C.byref(st.desc), _p(st.uvbuf), _p(st.tri_id), st.B * st.K,
                                                   st.H, st.W, _p(self.inv), _p(st.g_samp), _p(st.g_tex), s),
                    "texture_grad_invuv")
@@ -780,6 +780,21 @@ class BatchStep(_TwoStreams):
         fi.albedo, fi.albedo_stride, fi.albedo_channels = _cp(self.samp, 0), Ct, 4
         fi.tri_eye = C.c_void_p(self.tri_view.data_ptr())
         self._fin = fi
+        # stage packing (§3.3.3) as in Step: interpolation, texture, shading
+        # and blend as one forward pass, the weighted loss and their adjoints
+        # as one backward pass; scenes' extra["packed"] = False keeps the
+        # separate stages
+        self.packed = Ct == 4 and all(bool(s.extra.get("packed", True)) for s in scenes_list)
+        self.inv = None
+        if self.packed:
+            ps = Bd.PackedScene()
+            ps.mode, ps.vattr, ps.V, ps.Cv = Bd.SHADE_PHONG, _p(self.vattr), self.V, 6
+            ps.tris, ps.T, ps.eye, ps.tri_eye = _p(self.tris), self.T, _p(self.eye), _p(self.tri_view)
+            ps.uv, ps.uv_tris, ps.Vuv = _p(self.uv), _p(self.uv_tris), self.uv.shape[0]
+            ps.tex, ps.td = _p(self.tex), self.desc
+            self._pscene = ps
+            nb = int(_lib.dressi_invuv_bytes(C.byref(self.desc), 1))
+            self.inv = torch.empty(nb // 4, dtype=torch.int32, device=dev)
         self.hard_raster = None
         self.hybrid_weight = HYBRID_WEIGHT_DEFAULT
         self._calibrate_bins()
@@ -828,6 +843,12 @@ class BatchStep(_TwoStreams):
         self._fork("index")
         self._chk2(_lib.dressi_fragment_index(self._h2("index"), _p(self.tri_id), 1, 1, H, W, T, _p(self.frag_index),
                                               self._sa("index")), "fragment_index", "index")
+        if self.packed:
+            ck(_lib.dressi_packed_forward(h, C.byref(self._pscene), _p(self.tri_id), _p(self.bary), 1, H, W,
+                                          _p(self.gbuf), _p(self.uvbuf), _p(self.samp), _p(self.color),
+                                          _p(self.sil), _p(self.E), _p(self.inv), st), "packed_forward")
+            self._join()
+            return
         ck(_lib.dressi_interpolate(h, _p(self.vattr), 1, V, 6, _p(self.tris), T, _p(self.tri_id), _p(self.bary),
                                    1, 1, H, W, _p(self.gbuf), st), "interpolate")
         ck(_lib.dressi_interpolate(h, _p(self.uv), 1, self.uv.shape[0], 2, _p(self.uv_tris), T, _p(self.tri_id),
@@ -865,6 +886,33 @@ class BatchStep(_TwoStreams):
                                        _p(self.tri_id), _p(self.bary), 1, 1, H, W, _p(self.g_uvbuf), None,
                                        _p(self.frag_index), _p(self.uv_adj), None, _p(self.g_bary_uv), st),
            "interpolate_bwd uv")
+        self._backward_geometry()
+        self._join()
+
+    def _packed_backward(self):
+        """Weighted loss, blend, shading and texture-coordinate adjoints in
+        one pass (with the inverse-UV registration), then the texel gather
+        and the geometry's backward as in the separate form."""
+        h, st = self.ctx.handle, self._s()
+        H, W, T = self.H, self.W, self.T
+        self._chk(_lib.dressi_packed_backward(h, C.byref(self._pscene), _p(self.tri_id), 1, H, W, _p(self.gbuf),
+                                              _p(self.uvbuf), _p(self.samp), _p(self.color), _p(self.sil),
+                                              _p(self.target), _p(self.weight), _p(self.loss), None, None,
+                                              _p(self.g_gbuf), _p(self.g_samp), _p(self.g_bary_uv), _p(self.inv),
+                                              st), "packed_backward")
+        self._fork("texel")
+        self._chk2(_lib.dressi_texture_grad_invuv(self._h2("texel"), C.byref(self.desc), _p(self.uvbuf),
+                                                  _p(self.tri_id), 1, H, W, _p(self.inv), _p(self.g_samp),
+                                                  _p(self.g_tex), self._sa("texel")), "texture_grad_invuv", "texel")
+        self._backward_geometry()
+        self._join()
+
+    def _backward_geometry(self):
+        """Attribute interpolation, rasterization, transform and vertex
+        attribute adjoints from g_gbuf and the texture coordinates'
+        barycentric gradient g_bary_uv."""
+        h, st = self.ctx.handle, self._s()
+        H, W, V, T, ck = self.H, self.W, self.V, self.T, self._chk
         ck(_lib.dressi_interpolate_bwd(h, _p(self.vattr), 1, V, 6, _p(self.tris), T, _p(self.tri_id), _p(self.bary),
                                        1, 1, H, W, _p(self.g_gbuf), _p(self.g_bary_uv), _p(self.frag_index),
                                        _p(self.adj), _p(self.g_vattr), _p(self.g_bary), st), "interpolate_bwd")
@@ -876,10 +924,15 @@ class BatchStep(_TwoStreams):
                                              _p(self.g_pos_t), st), "transform_batched_bwd")
         ck(_lib.dressi_vertex_attrs_bwd(h, _p(self.pos), _p(self.tris), V, T, 6, _p(self.adj), _p(self.g_vattr),
                                         _p(self.g_pos_t), _p(self.g_pos), st), "vertex_attrs_bwd")
-        self._join()
 
     def run(self):
+        """One step; in the packed form (without inverse-UV jitter) the loss
+        and the backward are one pass, leaving g_color and g_sil unwritten."""
         self.forward()
+        if self.packed and self.frame == 0:
+            with self._sparse():
+                self._packed_backward()
+            return
         self.loss_and_grad()
         self.backward()
 
