@@ -11,11 +11,19 @@
 #include "texcore.h"
 
 
+// Large textures (4 Mi cells a face and more): the per-pixel kernels give
+// each XCD one contiguous range of pixels, whose texels are then fetched
+// into one L2; smaller textures keep the default interleave.
+#define IV_LARGE_CELLS (1 << 22)
+__device__ __forceinline__ int64_t tex_block(const dressi_tex_desc &td) {
+    return (int64_t)td.Ht * td.Wt >= IV_LARGE_CELLS ? xcd_block() : (int64_t)blockIdx.x;
+}
+
 template <int CT>
 __global__ void __launch_bounds__(256)
     k_tex_fwd(const float *__restrict__ tex, dressi_tex_desc td, const float *__restrict__ coord,
               const int32_t *__restrict__ tri_id, int64_t n, float *__restrict__ out, int skip_empty) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t i = tex_block(td) * blockDim.x + threadIdx.x;
     if (i >= n) return;
     if (skip_empty && tri_id && tri_id[i] < 0) return;
     const int Ct = CT > 0 ? CT : td.Ct;
@@ -43,7 +51,7 @@ __global__ void __launch_bounds__(256)
                                 const float *__restrict__ coord, const int32_t *__restrict__ tri_id,
                                 int64_t npix, int S, const float *__restrict__ grad_out,
                                 float *__restrict__ grad_coord, int32_t *__restrict__ inv, int skip_empty) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t i = tex_block(td) * blockDim.x + threadIdx.x;
     if (i >= (int64_t)S * npix) return;
     const int Ct = CT > 0 ? CT : td.Ct;
     const bool cube = td.kind == DRESSI_TEX_CUBE;
@@ -236,7 +244,7 @@ template <int CT, int SG, int R>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((R == 2 && CT > 0 && CT <= 4) ? 8 : 1)))
     k_invuv_gather(dressi_tex_desc td, const float *__restrict__ coord, const int32_t *__restrict__ tri_id,
                    int64_t npix, int S, int nsplit, const int32_t *__restrict__ inv,
-                   const float *__restrict__ grad_out, float *__restrict__ out) {
+                   const float *__restrict__ grad_out, float *__restrict__ out, int xcd) {
     // per halo cell of each slice of the group: the winner's four tap
     // coordinates, bilinear fractions (fx < 0: no winner, or one on another
     // cube face) and pixel gradient
@@ -251,10 +259,18 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((R == 
     const int wu = cube ? DRESSI_WRAP_CLAMP : td.wrap_u;
     const int wv = cube ? DRESSI_WRAP_CLAMP : td.wrap_v;
     const int cd = cube ? 3 : 2;
-    const int f = blockIdx.z / nsplit, part = blockIdx.z - f * nsplit;
+    // workgroups of neighbouring texel blocks share inverse-UV cells and their
+    // winners' pixel rows: with `xcd`, each XCD takes one contiguous range of
+    // the grid (rows of blocks), so they are fetched into one L2
+    const int64_t gxy = (int64_t)gridDim.x * gridDim.y;
+    const int64_t lin = ((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+    const int64_t lb = xcd ? xcd_block(lin, gxy * gridDim.z) : lin;
+    const int bz = (int)(lb / gxy), byi = (int)((lb - bz * gxy) / gridDim.x);
+    const int bxi = (int)(lb - bz * gxy - (int64_t)byi * gridDim.x);
+    const int f = bz / nsplit, part = bz - f * nsplit;
     const int per = (S + nsplit - 1) / nsplit;
     const int s0 = part * per, s1 = min(S, s0 + per);
-    const int bx0 = blockIdx.x * IV_T, by0 = blockIdx.y * G::TY;
+    const int bx0 = bxi * IV_T, by0 = byi * G::TY;
     const int lx = threadIdx.x % IV_T, ly = threadIdx.x / IV_T;
     const int tx = bx0 + lx;
     const int64_t face_cells = (int64_t)Ht * Wt;
@@ -386,43 +402,49 @@ __global__ void k_invuv_reduce(const float *__restrict__ part, int nsplit, int64
 template <int SG, int R>
 static void launch_gather_r(int ct, dim3 g, hipStream_t st, const dressi_tex_desc &td, const float *coord,
                             const int32_t *tri_id, int64_t npix, int S, int nsplit, const int32_t *inv,
-                            const float *grad_out, float *dst) {
+                            const float *grad_out, float *dst, int xcd) {
     constexpr int nt = IvGeom<SG, R>::NT;
     if (ct == 4)
         DR_LAUNCH("k_invuv_gather", (k_invuv_gather<4, SG, R>), g, nt, 0, st, td, coord, tri_id, npix, S,
-                  nsplit, inv, grad_out, dst);
+                  nsplit, inv, grad_out, dst, xcd);
     else if (ct == 3)
         DR_LAUNCH("k_invuv_gather", (k_invuv_gather<3, SG, R>), g, nt, 0, st, td, coord, tri_id, npix, S,
-                  nsplit, inv, grad_out, dst);
+                  nsplit, inv, grad_out, dst, xcd);
     else if (ct == 8)
         DR_LAUNCH("k_invuv_gather", (k_invuv_gather<8, SG, R>), g, nt, 0, st, td, coord, tri_id, npix, S,
-                  nsplit, inv, grad_out, dst);
+                  nsplit, inv, grad_out, dst, xcd);
     else
         DR_LAUNCH("k_invuv_gather", (k_invuv_gather<0, SG, 1>), g, nt, 0, st, td, coord, tri_id, npix, S,
-                  nsplit, inv, grad_out, dst);
+                  nsplit, inv, grad_out, dst, xcd);
 }
 
+// Large textures take the XCD-contiguous block order and two texel rows per
+// lane in the gather as well.
+
 // Texel rows per lane of the gather: `rows` (1, 2 or 4) or, for 0, 2 rows
-// for a single slice and 1 for several (measured: with one slice the larger
-// blocks are faster, with many the loop over slices prefers more, smaller
-// blocks in flight).  Any choice gives the same sums in the same order.
-static int gather_rows(int rows, int ct, int S) {
+// for a single slice or a large texture and 1 otherwise (measured: with one
+// slice the larger blocks are faster; with many slices of a 1024^2 texture
+// the loop over slices prefers more, smaller blocks in flight; a 4096^2
+// texture prefers the larger blocks again).  Any choice gives the same sums
+// in the same order.
+static int gather_rows(int rows, int ct, int S, const dressi_tex_desc &td) {
     if (ct != 3 && ct != 4 && ct != 8) return 1;
     if (rows == 1 || rows == 2 || rows == 4) return rows;
-    return S == 1 ? 2 : 1;
+    return (S == 1 || (int64_t)td.Ht * td.Wt >= IV_LARGE_CELLS) ? 2 : 1;
 }
 
 static void launch_gather(int rows, int ct, int64_t gx, int64_t ty_cells, int gz, hipStream_t st,
                           const dressi_tex_desc &td, const float *coord, const int32_t *tri_id, int64_t npix,
                           int S, int nsplit, const int32_t *inv, const float *grad_out, float *dst) {
-    const int R = gather_rows(rows, ct, S);
+    const int R = gather_rows(rows, ct, S, td);
+    const int xcd = (int64_t)td.Ht * td.Wt >= IV_LARGE_CELLS;
     dim3 g((unsigned)gx, (unsigned)((ty_cells + 16 * R - 1) / (16 * R)), (unsigned)gz);
     if (R == 4)
-        launch_gather_r<DRESSI_IV_SG, 4>(ct, g, st, td, coord, tri_id, npix, S, nsplit, inv, grad_out, dst);
+        launch_gather_r<DRESSI_IV_SG, 4>(ct, g, st, td, coord, tri_id, npix, S, nsplit, inv, grad_out, dst, xcd);
     else if (R == 2)
-        launch_gather_r<DRESSI_IV_SG, 2>(ct, g, st, td, coord, tri_id, npix, S, nsplit, inv, grad_out, dst);
+        launch_gather_r<DRESSI_IV_SG, 2>(ct, g, st, td, coord, tri_id, npix, S, nsplit, inv, grad_out, dst, xcd);
     else
-        launch_gather_r<DRESSI_IV_SG, 1>(ct, g, st, td, coord, tri_id, npix, S, nsplit, inv, grad_out, dst);
+        launch_gather_r<DRESSI_IV_SG, 1>(ct, g, st, td, coord, tri_id, npix, S, nsplit, inv, grad_out, dst, xcd);
 }
 
 // float4 rows need 16-byte aligned bases
