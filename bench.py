@@ -137,8 +137,8 @@ def scene_for(cfg):
 FETCH_SCALE, WRITE_SCALE = 262144.0 / 131083.5, 1.0
 TRAFFIC = {
     "k_invuv_gather": {"src": "paper_2204_01386_amd/csrc/texture.hip",
-                       "sha": "cb40e8264c0b66a037f82fecc78b5df5aa2727ec99bf94e05873883dfaa1c204",
-                       "fetch_kib": 10128.3125, "write_kib": 16384.0},
+                       "sha": "5d171934aed6ba8caa745edaef5ce14182b9e646c96ea2f363ebff17d255f6f9",
+                       "fetch_kib": 10169.8125, "write_kib": 16384.0},
 }
 
 
