@@ -137,7 +137,7 @@ def scene_for(cfg):
 FETCH_SCALE, WRITE_SCALE = 262144.0 / 131083.5, 1.0
 TRAFFIC = {
     "k_invuv_gather": {"src": "paper_2204_01386_amd/csrc/texture.hip",
-                       "sha": "5d171934aed6ba8caa745edaef5ce14182b9e646c96ea2f363ebff17d255f6f9",
+                       "sha": "3e1f1da8ddcdbb408df3d093379443faeca24ff9ad1f3fd4a8461a9b357f26b3",
                        "fetch_kib": 10169.8125, "write_kib": 16384.0},
 }
 

@@ -241,7 +241,7 @@ struct IvGeom {
 };
 
 template <int CT, int SG, int R>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((R == 2 && CT > 0 && CT <= 4) ? 8 : 1)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(((R == 1 && CT == 8) || (R == 2 && CT > 0 && CT <= 4)) ? 8 : 1)))
     k_invuv_gather(dressi_tex_desc td, const float *__restrict__ coord, const int32_t *__restrict__ tri_id,
                    int64_t npix, int S, int nsplit, const int32_t *__restrict__ inv,
                    const float *__restrict__ grad_out, float *__restrict__ out, int xcd) {
