@@ -282,6 +282,8 @@ def kernel_bytes(name, z: Shapes):
         return z.adj + V * Cv * 4
     if name == "k_rast_bwd_tile":
         return B * V * 16 + T * 12 + N * 4 + c * (8 + d)
+    if name == "k_geo_vertex":        # the vertex sums of both adjoints and the transform adjoint
+        return z.adj + V * Cv * 4 + B * V * 16 + B * V * 16 + B * 64 + V * 12
     if name == "k_rast_bwd_vertex":
         return z.adj + B * V * 16 + B * V * 16
     if name == "k_fragsort":

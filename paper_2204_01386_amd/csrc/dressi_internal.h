@@ -155,6 +155,12 @@ struct TriTiles {
     int32_t *offsets;   // [B*T+1]
     int2 *entries;      // [B*nTiles*256*K]
 };
+// Per-tile interpolation adjoint (interp.hip): grad_bary and each tile's
+// per-triangle records of b_i g in `part` [B*nTiles*256*K][3][C].
+void dr_interp_bwd_tiles(const float *attr, int Ba, int Va, int C, const int32_t *attr_tris, int T,
+                         const int32_t *tri_id, const float *bary, int B, int K, int H, int W, const FragLists &fl,
+                         const float *grad_out, const float *grad_bary_in, float *grad_bary, float *part,
+                         int skip_empty, hipStream_t st);
 size_t dressi_fragindex_bytes(int B, int K, int H, int W, int T);
 void dressi_fragindex_view(void *base, int B, int K, int H, int W, int T, FragLists &fl, TriTiles &tt);
 size_t dressi_fragindex_tmp_bytes(int B, int K, int H, int W, int T);

@@ -388,6 +388,39 @@ __global__ void k_interp_bwd_vertex_c(int B, int Ba, int Va, int T, int K, TriTi
     }
 }
 
+// Per-tile interpolation adjoint (k_interp_bwd_tile): grad_bary and each
+// tile's per-triangle records of b_i g (`part`), which the per-vertex sums
+// read.  Shared by dressi_interpolate_bwd and dressi_geometry_bwd.
+void dr_interp_bwd_tiles(const float *attr, int Ba, int Va, int C, const int32_t *attr_tris, int T,
+                         const int32_t *tri_id, const float *bary, int B, int K, int H, int W, const FragLists &fl,
+                         const float *grad_out, const float *grad_bary_in, float *grad_bary, float *part,
+                         int skip_empty, hipStream_t st) {
+    const int ntx = tiles_x(W), nt = ntx * tiles_y(H);
+    if ((int64_t)B * nt > 0) {
+        const size_t lds = sizeof(float) * (size_t)ib_stride(C) * DRESSI_TILE_PIX * K;
+        const bool al8 = (((uintptr_t)attr | (uintptr_t)grad_out) & 7u) == 0;
+        const float2 *b2 = reinterpret_cast<const float2 *>(bary);
+        const float2 *gbi = reinterpret_cast<const float2 *>(grad_bary_in);
+        float2 *gbo = reinterpret_cast<float2 *>(grad_bary);
+        if (al8 && C == 6)
+            DR_LAUNCH("k_interp_bwd_tile", (k_interp_bwd_tile<6>), B * nt, DRESSI_TILE_PIX, lds, st, attr, Ba,
+                      Va, C, attr_tris, T, tri_id, b2, K, H, W, ntx, nt, fl, grad_out, gbi, gbo, part,
+                      skip_empty);
+        else if (al8 && C == 2)
+            DR_LAUNCH("k_interp_bwd_tile", (k_interp_bwd_tile<2>), B * nt, DRESSI_TILE_PIX, lds, st, attr, Ba,
+                      Va, C, attr_tris, T, tri_id, b2, K, H, W, ntx, nt, fl, grad_out, gbi, gbo, part,
+                      skip_empty);
+        else if (C == 9)
+            DR_LAUNCH("k_interp_bwd_tile", (k_interp_bwd_tile<9>), B * nt, DRESSI_TILE_PIX, lds, st, attr, Ba,
+                      Va, C, attr_tris, T, tri_id, b2, K, H, W, ntx, nt, fl, grad_out, gbi, gbo, part,
+                      skip_empty);
+        else
+            DR_LAUNCH("k_interp_bwd_tile", (k_interp_bwd_tile<0>), B * nt, DRESSI_TILE_PIX, lds, st, attr, Ba,
+                      Va, C, attr_tris, T, tri_id, b2, K, H, W, ntx, nt, fl, grad_out, gbi, gbo, part,
+                      skip_empty);
+    }
+}
+
 extern "C" int dressi_interpolate_bwd(dressi_ctx *ctx, const float *attr, int Ba, int Va, int C,
                                       const int32_t *attr_tris, int T, const int32_t *tri_id,
                                       const float *bary, int B, int K, int H, int W,
@@ -432,29 +465,8 @@ extern "C" int dressi_interpolate_bwd(dressi_ctx *ctx, const float *attr, int Ba
         }
         Adjacency A = adjacency_view(ab, Va);
         float *part = at<float>(S, o_part);
-        if ((int64_t)B * nt > 0) {
-            const size_t lds = sizeof(float) * (size_t)ib_stride(C) * DRESSI_TILE_PIX * K;
-            const bool al8 = (((uintptr_t)attr | (uintptr_t)grad_out) & 7u) == 0;
-            const float2 *b2 = reinterpret_cast<const float2 *>(bary);
-            const float2 *gbi = reinterpret_cast<const float2 *>(grad_bary_in);
-            float2 *gbo = reinterpret_cast<float2 *>(grad_bary);
-            if (al8 && C == 6)
-                DR_LAUNCH("k_interp_bwd_tile", (k_interp_bwd_tile<6>), B * nt, DRESSI_TILE_PIX, lds, st, attr, Ba,
-                          Va, C, attr_tris, T, tri_id, b2, K, H, W, ntx, nt, fl, grad_out, gbi, gbo, part,
-                          ctx->skip_empty);
-            else if (al8 && C == 2)
-                DR_LAUNCH("k_interp_bwd_tile", (k_interp_bwd_tile<2>), B * nt, DRESSI_TILE_PIX, lds, st, attr, Ba,
-                          Va, C, attr_tris, T, tri_id, b2, K, H, W, ntx, nt, fl, grad_out, gbi, gbo, part,
-                          ctx->skip_empty);
-            else if (C == 9)
-                DR_LAUNCH("k_interp_bwd_tile", (k_interp_bwd_tile<9>), B * nt, DRESSI_TILE_PIX, lds, st, attr, Ba,
-                          Va, C, attr_tris, T, tri_id, b2, K, H, W, ntx, nt, fl, grad_out, gbi, gbo, part,
-                          ctx->skip_empty);
-            else
-                DR_LAUNCH("k_interp_bwd_tile", (k_interp_bwd_tile<0>), B * nt, DRESSI_TILE_PIX, lds, st, attr, Ba,
-                          Va, C, attr_tris, T, tri_id, b2, K, H, W, ntx, nt, fl, grad_out, gbi, gbo, part,
-                          ctx->skip_empty);
-        }
+        dr_interp_bwd_tiles(attr, Ba, Va, C, attr_tris, T, tri_id, bary, B, K, H, W, fl, grad_out, grad_bary_in,
+                            grad_bary, part, ctx->skip_empty, st);
         const int64_t nv = (int64_t)Ba * Va, gv = (nv * IBV_LANES + 255) / 256;
         if (C == 6)
             DR_LAUNCH("k_interp_bwd_vertex", (k_interp_bwd_vertex_c<6>), (int)gv, 256, 0, st, B, Ba, Va, T, K, tt,

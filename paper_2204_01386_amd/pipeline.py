@@ -275,6 +275,8 @@ class Step(_TwoStreams):
                 nb = int(_lib.dressi_invuv_bytes(C.byref(self.desc), B))
                 self.inv = torch.empty(nb // 4, dtype=torch.int32, device=dev)
             self._pscene = ps
+        # one view: the geometry adjoints as one call (dressi_geometry_bwd)
+        self.packed_geo = self.packed and B == 1
         self.hard_raster = None     # rasterization strategy chosen by autotune() (None: triangle-parallel)
         self.hybrid_weight = HYBRID_WEIGHT_DEFAULT
         self._calibrate_bins()
@@ -448,7 +450,17 @@ class Step(_TwoStreams):
                                                       _p(self.g_tex), self._sa("texel")),
                        "texture_grad_invuv", "texel")
             gb_in = self.g_bary_uv
-        self._backward_geometry(gb_in)
+        if self.packed_geo:
+            ck(_lib.dressi_geometry_bwd(h, _p(self.vattr), self.V, self.Cv, _p(self.tris), self.T, _p(self.pos_clip),
+                                        _p(self.mvp), None, None, None, 0, H, W, 0, _p(self.tri_id), _p(self.bary),
+                                        _p(self.g_gbuf), _p(gb_in), _p(self.frag_index), _p(self.adj),
+                                        _p(self.g_vattr), _p(self.g_bary), _p(self.g_clip), _p(self.g_pos_t), s),
+               "geometry_bwd")
+            ck(_lib.dressi_vertex_attrs_bwd(h, _p(self.pos), _p(self.tris), self.V, self.T, self.Cv, _p(self.adj),
+                                            _p(self.g_vattr), _p(self.g_pos_t), _p(self.g_pos), s),
+               "vertex_attrs_bwd")
+        else:
+            self._backward_geometry(gb_in)
         self._join()
 
     def _backward_geometry(self, gb_in):
@@ -477,8 +489,9 @@ class Step(_TwoStreams):
         """One full step: forward, loss and gradient, backward.  In the packed
         form (and without inverse-UV jitter) the loss and the backward are one
         pass, which leaves g_color and g_sil unwritten."""
+        packed = self.packed and self.frame == 0
         self.forward()
-        if self.packed and self.frame == 0:
+        if packed:
             with self._sparse():
                 self._packed_backward()
             return
@@ -904,7 +917,15 @@ class BatchStep(_TwoStreams):
         self._chk2(_lib.dressi_texture_grad_invuv(self._h2("texel"), C.byref(self.desc), _p(self.uvbuf),
                                                   _p(self.tri_id), 1, H, W, _p(self.inv), _p(self.g_samp),
                                                   _p(self.g_tex), self._sa("texel")), "texture_grad_invuv", "texel")
-        self._backward_geometry()
+        ck = self._chk
+        V, T = self.V, self.T
+        ck(_lib.dressi_geometry_bwd(h, _p(self.vattr), V, 6, _p(self.tris), T, _p(self.pos_clip), _p(self.mvp),
+                                    _p(self.vert_view), _p(self.tri_view), _p(self.views), self.n, H, W, 0,
+                                    _p(self.tri_id), _p(self.bary), _p(self.g_gbuf), _p(self.g_bary_uv),
+                                    _p(self.frag_index), _p(self.adj), _p(self.g_vattr), _p(self.g_bary),
+                                    _p(self.g_clip), _p(self.g_pos_t), st), "geometry_bwd")
+        ck(_lib.dressi_vertex_attrs_bwd(h, _p(self.pos), _p(self.tris), V, T, 6, _p(self.adj), _p(self.g_vattr),
+                                        _p(self.g_pos_t), _p(self.g_pos), st), "vertex_attrs_bwd")
         self._join()
 
     def _backward_geometry(self):
@@ -928,8 +949,9 @@ class BatchStep(_TwoStreams):
     def run(self):
         """One step; in the packed form (without inverse-UV jitter) the loss
         and the backward are one pass, leaving g_color and g_sil unwritten."""
+        packed = self.packed and self.frame == 0
         self.forward()
-        if self.packed and self.frame == 0:
+        if packed:
             with self._sparse():
                 self._packed_backward()
             return
