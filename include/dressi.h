@@ -545,7 +545,7 @@ int dressi_packed_backward(dressi_ctx *ctx, const dressi_packed_scene *scene, co
                            float *grad_samp, float *grad_bary_uv, int32_t *inv, void *stream);
 
 /* Geometry adjoints of one image (B = 1, K = 1, hard: after the packed
- * pass), in three launches: the same values as dressi_interpolate_bwd of
+ * pass), in two launches: the same values as dressi_interpolate_bwd of
  * vattr [V, Cv] (Cv = 6 or 9, indexed by tris, grad_out = grad_gbuf
  * [H,W,Cv], grad_bary_in nullable: the texture coordinates' barycentric
  * gradient), then dressi_rasterize_bwd (r = 0), then dressi_transform_bwd.
@@ -554,8 +554,9 @@ int dressi_packed_backward(dressi_ctx *ctx, const dressi_packed_scene *scene, co
  * (n_views rectangles, as dressi_rasterize_batched) and vert_view (the
  * matrix of each vertex, as dressi_transform_batched); otherwise all three
  * are NULL and mvp is one matrix.  frag_index: dressi_fragment_index of
- * this tri_id (B = K = 1); adj: dressi_adjacency of tris.  The per-vertex
- * sums of both adjoints and the transform adjoint run in one kernel. */
+ * this tri_id (B = K = 1); adj: dressi_adjacency of tris.  Two kernels:
+ * both per-tile adjoints in one, then the per-vertex sums of both and the
+ * transform adjoint in the other. */
 int dressi_geometry_bwd(dressi_ctx *ctx, const float *vattr, int V, int Cv, const int32_t *tris, int T,
                         const float *pos_clip, const float *mvp, const int32_t *vert_view, const int32_t *tri_view,
                         const int32_t *views, int n_views, int H, int W, int cull, const int32_t *tri_id,

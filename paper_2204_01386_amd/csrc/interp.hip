@@ -7,11 +7,10 @@
 // attribute vertex and channel, every corner's records are summed in tile
 // order (through the triangle->tile transpose) and the corners in ascending
 // order.  No float atomics.
-#include "dressi_internal.h"
+#include "interp_tile.h"
 
 #include <algorithm>
 
-#define IB_CH 16   // channels per pass of the per-triangle gather
 
 // One lane per fragment; the block's outputs (256 fragments x C channels, a
 // contiguous range) are staged in LDS and written back with coalesced float4
@@ -171,27 +170,6 @@ __global__ void k_interp_bwd_bary(const float *__restrict__ attr, int Ba, int Va
     grad_bary[o] = make_float2(acc.x + g0, acc.y + g1);
 }
 
-// Row of C floats; CC = C at compile time (0: run time), 8-byte aligned rows
-// with an even CC are read in pairs, odd ones one float at a time.
-template <int CC>
-__device__ __forceinline__ void ld_row(const float *src, float *v, int C) {
-    if constexpr (CC > 0 && (CC & 1) == 0) {
-#pragma unroll
-        for (int c = 0; c < CC; c += 2) {
-            const float2 q = *reinterpret_cast<const float2 *>(src + c);
-            v[c] = q.x;
-            v[c + 1] = q.y;
-        }
-    } else if constexpr (CC > 0) {
-#pragma unroll
-        for (int c = 0; c < CC; c++) v[c] = src[c];
-    }
-}
-
-// LDS row stride of a fragment: odd, so that lanes writing consecutive rows
-// fall in distinct banks
-__host__ __device__ static inline int ib_stride(int C) { return (C + 2) | 1; }
-
 // per tile: every fragment's (b0, b1, g_0..g_{C-1}) in LDS; each triangle's
 // fragments (consecutive in the tile's sorted list) are summed into one
 // record of b_i g_c for its three corners.  Also writes grad_bary.
@@ -217,53 +195,9 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX)
     if (x < W && y < H) {
         for (int k = 0; k < K; k++) {
             int64_t o = (((int64_t)b * K + k) * H + y) * W + x;
-            int t = tri_id[o];
-            int v0 = -1, v1 = -1, v2 = -1;
-            if (t >= 0 && t < T) {
-                v0 = attr_tris[3 * (int64_t)t];
-                v1 = attr_tris[3 * (int64_t)t + 1];
-                v2 = attr_tris[3 * (int64_t)t + 2];
-            }
-            if (skip_empty && t < 0) continue;
-            bool ok = v0 >= 0 && v0 < Va && v1 >= 0 && v1 < Va && v2 >= 0 && v2 < Va;
-            float2 acc = gb_in ? gb_in[o] : make_float2(0.0f, 0.0f);
-            const float *g = grad_out + o * C;
-            float *dst = vals + (k * DRESSI_TILE_PIX + p) * S;
-            if (ok) {
-                float2 w = bary[o];
-                dst[0] = w.x;
-                dst[1] = w.y;
-                const float *a0 = ab + (int64_t)v0 * C, *a1 = ab + (int64_t)v1 * C, *a2 = ab + (int64_t)v2 * C;
-                float g0 = 0.0f, g1 = 0.0f;
-                if constexpr (CC > 0) {
-                    float gv[CC], r0[CC], r1[CC], r2[CC];
-                    ld_row<CC>(g, gv, C);
-                    ld_row<CC>(a0, r0, C);
-                    ld_row<CC>(a1, r1, C);
-                    ld_row<CC>(a2, r2, C);
-#pragma unroll
-                    for (int c = 0; c < CC; c++) {
-                        dst[2 + c] = gv[c];
-                        g0 += gv[c] * (r0[c] - r2[c]);
-                        g1 += gv[c] * (r1[c] - r2[c]);
-                    }
-                } else {
-                    for (int c = 0; c < C; c++) {
-                        float gc = g[c];
-                        dst[2 + c] = gc;
-                        g0 += gc * (a0[c] - a2[c]);
-                        g1 += gc * (a1[c] - a2[c]);
-                    }
-                }
-                acc.x += g0;
-                acc.y += g1;
-            } else if (t >= 0) {
-                // a fragment whose attribute triangle is invalid contributes nothing
-                dst[0] = 0.0f;
-                dst[1] = 0.0f;
-                for (int c = 0; c < C; c++) dst[2 + c] = 0.0f;
-            }
-            if (grad_bary) grad_bary[o] = acc;
+            float2 acc;
+            ib_fragment<CC>(ab, Va, C, attr_tris, T, tri_id[o], o, bary, grad_out, gb_in, grad_bary,
+                            vals + (k * DRESSI_TILE_PIX + p) * S, skip_empty, acc);
         }
     }
     __syncthreads();
@@ -273,32 +207,7 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX)
     for (int r = p; r < nr; r += DRESSI_TILE_PIX) {
         int j0 = fl.rec_start[base + r];
         int j1 = (r + 1 < nr) ? fl.rec_start[base + r + 1] : nf;
-        float *dst = partial + (base + r) * 3 * C;
-        for (int c0 = 0; c0 < C; c0 += IB_CH) {
-            float acc[3][IB_CH];
-#pragma unroll
-            for (int i = 0; i < 3; i++)
-#pragma unroll
-                for (int c = 0; c < IB_CH; c++) acc[i][c] = 0.0f;
-            for (int j = j0; j < j1; j++) {
-                const float *v = vals + (int)fl.frag[base + j] * S;
-                float w0 = v[0], w1 = v[1], w2 = 1.0f - w0 - w1;
-#pragma unroll
-                for (int c = 0; c < IB_CH; c++) {
-                    if (c0 + c < C) {
-                        float gc = v[2 + c0 + c];
-                        acc[0][c] += w0 * gc;
-                        acc[1][c] += w1 * gc;
-                        acc[2][c] += w2 * gc;
-                    }
-                }
-            }
-#pragma unroll
-            for (int i = 0; i < 3; i++)
-#pragma unroll
-                for (int c = 0; c < IB_CH; c++)
-                    if (c0 + c < C) dst[i * C + c0 + c] = acc[i][c];
-        }
+        ib_record(vals, S, C, fl, base, j0, j1, partial + (base + r) * 3 * C);
     }
 }
 

@@ -18,7 +18,7 @@
 // corners sums its records over the tiles in a fixed order and the corners
 // are combined in a fixed order.  No float atomics: results are bitwise
 // reproducible.
-#include "dressi_internal.h"
+#include "interp_tile.h"
 
 #include <algorithm>
 #include <type_traits>
@@ -1562,7 +1562,7 @@ int64_t dr_tile_capacity(const dressi_limits &l) {
 // rasterize (full, banded or batched), rasterize_bwd and fragment_index
 // ---------------------------------------------------------------------------
 // geometry adjoint of one image (B = 1, K = 1, hard): interpolation,
-// rasterization and transform adjoints in three launches
+// rasterization and transform adjoints in two launches
 // ---------------------------------------------------------------------------
 // Eight lanes per vertex.  Attribute gradient: lanes 0-3 take the corners j,
 // j + 4, ... and are combined as k_interp_bwd_vertex_c combines its four;
@@ -1653,6 +1653,70 @@ __global__ void __launch_bounds__(256)
     grad_pos[3 * v + 2] = hz;
 }
 
+// Per tile (B = K = 1): the interpolation adjoint of every fragment (its
+// barycentric gradient and staged row, as k_interp_bwd_tile), then, from that
+// barycentric gradient, the rasterization adjoint of the same fragment (as
+// k_rast_bwd_tile); after one barrier each triangle record sums both in the
+// tile's sorted order.  The same values as the two kernels in sequence.
+template <int CC>
+__global__ void __launch_bounds__(DRESSI_TILE_PIX) __attribute__((amdgpu_waves_per_eu(5)))
+    k_geo_tile(const float *__restrict__ attr, int Va, const int32_t *__restrict__ tris, int T,
+               const float4 *__restrict__ pos_clip, Viewports vp, int H, int W, int cull,
+               const int32_t *__restrict__ tri_id, const float2 *__restrict__ bary, int ntx, FragLists fl,
+               const float *__restrict__ grad_out, const float2 *__restrict__ gb_in, float2 *__restrict__ grad_bary,
+               float *__restrict__ ipart, float *__restrict__ rpart, int skip_empty) {
+    extern __shared__ float vals[];   // [256][ib_stride(CC)] interpolation rows, then [256][9]
+    constexpr int S = (CC + 2) | 1;
+    float *rvals = vals + DRESSI_TILE_PIX * S;
+    const int bt = (int)blockIdx.x;
+    const int tx = bt % ntx, ty = bt / ntx;
+    const int p = threadIdx.x;
+    const int x = tx * DRESSI_TILE + (p & (DRESSI_TILE - 1));
+    const int y = ty * DRESSI_TILE + p / DRESSI_TILE;
+    if (x < W && y < H) {
+        const int64_t o = (int64_t)y * W + x;
+        const int t = tri_id[o];
+        float2 acc;
+        ib_fragment<CC>(attr, Va, CC, tris, T, t, o, bary, grad_out, gb_in, grad_bary, vals + p * S, skip_empty,
+                        acc);
+        if (t >= 0 && t < T) {
+            const int32_t *tv = tris + 3 * (int64_t)t;
+            const int4 q = dr_viewport(vp, t, H, W);
+            TriSetup s = dr_setup(pos_clip, tv[0], tv[1], tv[2], q.w, q.z, q.x, q.y, cull, 0);
+            float *dst = rvals + p * 9;
+            if (!(s.meta & 1)) {
+#pragma unroll
+                for (int c = 0; c < 9; c++) dst[c] = 0.0f;
+            } else {
+                float g9[9];
+                rast_frag_grad(s, x, y, acc, 0.0f, false, W, g9);
+#pragma unroll
+                for (int c = 0; c < 9; c++) dst[c] = g9[c];
+            }
+        }
+    }
+    __syncthreads();
+    const int nf = fl.n_frag[bt];
+    const int nr = fl.n_rec[bt];
+    const int64_t base = (int64_t)bt * DRESSI_TILE_PIX;
+    for (int r = p; r < nr; r += DRESSI_TILE_PIX) {
+        const int j0 = fl.rec_start[base + r];
+        const int j1 = (r + 1 < nr) ? fl.rec_start[base + r + 1] : nf;
+        ib_record(vals, S, CC, fl, base, j0, j1, ipart + (base + r) * 3 * CC);
+        float acc9[9];
+#pragma unroll
+        for (int c = 0; c < 9; c++) acc9[c] = 0.0f;
+        for (int j = j0; j < j1; j++) {
+            const float *v = rvals + (int)fl.frag[base + j] * 9;
+#pragma unroll
+            for (int c = 0; c < 9; c++) acc9[c] += v[c];
+        }
+        float *dst = rpart + (base + r) * 9;
+#pragma unroll
+        for (int c = 0; c < 9; c++) dst[c] = acc9[c];
+    }
+}
+
 static size_t geometry_scratch(int H, int W, int Cv, Carver &c, size_t *o) {
     const size_t n = (size_t)tiles_x(W) * tiles_y(H) * DRESSI_TILE_PIX;
     o[0] = c.take(sizeof(float) * n * 3 * Cv);
@@ -1693,12 +1757,28 @@ extern "C" int dressi_geometry_bwd(dressi_ctx *ctx, const float *vattr, int V, i
     dressi_fragindex_view(const_cast<void *>(frag_index), 1, 1, H, W, T, fl, tt);
     const Viewports vp{tri_view, reinterpret_cast<const int4 *>(views)};
     const int ntx = tiles_x(W), nt = ntx * tiles_y(H);
-    dr_interp_bwd_tiles(vattr, 1, V, Cv, tris, T, tri_id, bary, 1, 1, H, W, fl, grad_gbuf, grad_bary_in, grad_bary,
-                        ipart, ctx->skip_empty, st);
-    if (nt > 0)
-        DR_LAUNCH("k_rast_bwd_tile", (k_rast_bwd_tile), nt, DRESSI_TILE_PIX, sizeof(float) * 9 * DRESSI_TILE_PIX, st,
-                  reinterpret_cast<const float4 *>(pos_clip), tris, vp, V, T, H, W, 1, cull, 0, tri_id, fl, ntx, nt,
-                  reinterpret_cast<const float2 *>(grad_bary), nullptr, rpart);
+    // both per-tile adjoints in one kernel (6-channel rows are read in pairs:
+    // 8-byte aligned bases), else one after the other
+    const bool al8 = (((uintptr_t)vattr | (uintptr_t)grad_gbuf) & 7u) == 0;
+    const float4 *pc4 = reinterpret_cast<const float4 *>(pos_clip);
+    const float2 *b2 = reinterpret_cast<const float2 *>(bary);
+    const float2 *gbi = reinterpret_cast<const float2 *>(grad_bary_in);
+    float2 *gbo = reinterpret_cast<float2 *>(grad_bary);
+    if (nt > 0 && (Cv == 9 || al8)) {
+        const size_t lds = sizeof(float) * DRESSI_TILE_PIX * (((Cv + 2) | 1) + 9);
+        if (Cv == 6)
+            DR_LAUNCH("k_geo_tile", (k_geo_tile<6>), nt, DRESSI_TILE_PIX, lds, st, vattr, V, tris, T, pc4, vp, H, W,
+                      cull, tri_id, b2, ntx, fl, grad_gbuf, gbi, gbo, ipart, rpart, ctx->skip_empty);
+        else
+            DR_LAUNCH("k_geo_tile", (k_geo_tile<9>), nt, DRESSI_TILE_PIX, lds, st, vattr, V, tris, T, pc4, vp, H, W,
+                      cull, tri_id, b2, ntx, fl, grad_gbuf, gbi, gbo, ipart, rpart, ctx->skip_empty);
+    } else {
+        dr_interp_bwd_tiles(vattr, 1, V, Cv, tris, T, tri_id, bary, 1, 1, H, W, fl, grad_gbuf, grad_bary_in,
+                            grad_bary, ipart, ctx->skip_empty, st);
+        if (nt > 0)
+            DR_LAUNCH("k_rast_bwd_tile", (k_rast_bwd_tile), nt, DRESSI_TILE_PIX, sizeof(float) * 9 * DRESSI_TILE_PIX,
+                      st, pc4, tris, vp, V, T, H, W, 1, cull, 0, tri_id, fl, ntx, nt, gbo, nullptr, rpart);
+    }
     const Adjacency A = adjacency_view(adj, V);
     const int g = (int)(((int64_t)V * GV_LANES + 255) / 256);
     if (Cv == 6)
