@@ -545,24 +545,28 @@ int dressi_packed_backward(dressi_ctx *ctx, const dressi_packed_scene *scene, co
                            float *grad_samp, float *grad_bary_uv, int32_t *inv, void *stream);
 
 /* Geometry adjoints of one image (B = 1, K = 1, hard: after the packed
- * pass), in two launches: the same values as dressi_interpolate_bwd of
+ * pass), in three launches: the same values as dressi_interpolate_bwd of
  * vattr [V, Cv] (Cv = 6 or 9, indexed by tris, grad_out = grad_gbuf
  * [H,W,Cv], grad_bary_in nullable: the texture coordinates' barycentric
- * gradient), then dressi_rasterize_bwd (r = 0), then dressi_transform_bwd.
- * Writes grad_vattr [V,Cv], grad_bary [H,W,2], grad_pos_clip [V,4] and
- * grad_pos [V,3].  An uneven batch's packed image passes tri_view, views
- * (n_views rectangles, as dressi_rasterize_batched) and vert_view (the
- * matrix of each vertex, as dressi_transform_batched); otherwise all three
- * are NULL and mvp is one matrix.  frag_index: dressi_fragment_index of
- * this tri_id (B = K = 1); adj: dressi_adjacency of tris.  Two kernels:
- * both per-tile adjoints in one, then the per-vertex sums of both and the
- * transform adjoint in the other. */
-int dressi_geometry_bwd(dressi_ctx *ctx, const float *vattr, int V, int Cv, const int32_t *tris, int T,
-                        const float *pos_clip, const float *mvp, const int32_t *vert_view, const int32_t *tri_view,
-                        const int32_t *views, int n_views, int H, int W, int cull, const int32_t *tri_id,
-                        const float *bary, const float *grad_gbuf, const float *grad_bary_in, const void *frag_index,
-                        const int32_t *adj, float *grad_vattr, float *grad_bary, float *grad_pos_clip,
-                        float *grad_pos, void *stream);
+ * gradient), then dressi_rasterize_bwd (r = 0), then dressi_transform_bwd,
+ * then dressi_vertex_attrs_bwd of the world positions pos [V,3] that vattr
+ * was made from (dressi_vertex_attrs) with the transform's gradient as its
+ * grad_pos_in.  Writes grad_vattr [V,Cv], grad_bary [H,W,2], grad_pos_clip
+ * [V,4] and grad_pos [V,3], the gradient of the loss in pos.  An uneven
+ * batch's packed image passes tri_view, views (n_views rectangles, as
+ * dressi_rasterize_batched) and vert_view (the matrix of each vertex, as
+ * dressi_transform_batched); otherwise all three are NULL and mvp is one
+ * matrix.  frag_index: dressi_fragment_index of this tri_id (B = K = 1);
+ * adj: dressi_adjacency of tris.  Kernels: both per-tile adjoints in one;
+ * the per-vertex sums of both, the transform adjoint and the gradient of the
+ * un-normalised normal sum in the second; the cross-product adjoint of the
+ * vertex normals in the third. */
+int dressi_geometry_bwd(dressi_ctx *ctx, const float *pos, const float *vattr, int V, int Cv,
+                        const int32_t *tris, int T, const float *pos_clip, const float *mvp,
+                        const int32_t *vert_view, const int32_t *tri_view, const int32_t *views, int n_views,
+                        int H, int W, int cull, const int32_t *tri_id, const float *bary, const float *grad_gbuf,
+                        const float *grad_bary_in, const void *frag_index, const int32_t *adj, float *grad_vattr,
+                        float *grad_bary, float *grad_pos_clip, float *grad_pos, void *stream);
 
 /* ----------------------------------------------------------------------------
  * The optimisation loop around the step (§4.1: vertex positions fitted to

@@ -118,8 +118,8 @@ _SIG = {
     "dressi_shade": [_vp, _i, _vp, _vp, _vp, _i, _i64, _vp, _vp, _vp],
     "dressi_shade_bwd": [_vp, _i, _vp, _vp, _vp, _i, _i64, _vp, _vp, _vp, _vp],
     "dressi_loss_l2": [_vp, _vp, _vp, _vp, _vp, _i, _i, _i, _vp, _vp, _vp, _vp],
-    "dressi_geometry_bwd": [_vp, _vp, _i, _i, _vp, _i, _vp, _vp, _vp, _vp, _vp, _i, _i, _i, _i, _vp, _vp, _vp,
-                            _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
+    "dressi_geometry_bwd": [_vp, _vp, _vp, _i, _i, _vp, _i, _vp, _vp, _vp, _vp, _vp, _i, _i, _i, _i, _vp, _vp,
+                            _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
     "dressi_packed_forward": [_vp, _vp, _vp, _vp, _i, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
     "dressi_packed_backward": [_vp, _vp, _vp, _i, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                _vp, _vp, _vp, _vp, _vp],

@@ -229,6 +229,15 @@ __device__ __forceinline__ int4 dr_viewport(const Viewports &vp, int t, int H, i
     return vp.views[vp.tri_view[t]];
 }
 
+// Per-vertex part of the geometry adjoint of one image (shade.hip): both
+// vertex sums, the transform adjoint and the vertex-normal adjoint, writing
+// grad_attr, grad_pos_clip and the world-position gradient grad_pos
+// (grad_pos_t and gacc: scratch of 3V floats each).
+void dr_geo_vertex(int Cv, const float *pos, const int32_t *tris, const float *pos_clip, Viewports vp, int V, int H,
+                   int W, TriTiles tt, const float *ipart, const float *rpart, Adjacency adj, const float *mvp,
+                   const int32_t *vert_view, float *grad_attr, float *grad_pos_clip, float *grad_pos_t, float *gacc,
+                   float *grad_pos, hipStream_t st);
+
 // Builds the record of triangle `tv` (three vertex ids) for a view of H x W
 // pixels placed at pixel (ox, oy) of the image (0, 0 for a whole image):
 // coordinates are snapped in the view's own frame, then moved by the integer

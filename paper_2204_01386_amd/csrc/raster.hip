@@ -1562,97 +1562,8 @@ int64_t dr_tile_capacity(const dressi_limits &l) {
 // rasterize (full, banded or batched), rasterize_bwd and fragment_index
 // ---------------------------------------------------------------------------
 // geometry adjoint of one image (B = 1, K = 1, hard): interpolation,
-// rasterization and transform adjoints in two launches
+// rasterization, transform and vertex-normal adjoints in three launches
 // ---------------------------------------------------------------------------
-// Eight lanes per vertex.  Attribute gradient: lanes 0-3 take the corners j,
-// j + 4, ... and are combined as k_interp_bwd_vertex_c combines its four;
-// clip-space gradient: all eight take the corners j, j + 8, ... as
-// k_rast_bwd_vertex does; then the transform adjoint of k_transform_bwd.
-// Each corner's triangle's tile records are summed in tile order through the
-// triangle -> tile lists, so every value is summed over the same terms in
-// the same order as those three kernels.
-#define GV_LANES 8
-template <int CC>
-__global__ void __launch_bounds__(256)
-    k_geo_vertex(const float4 *__restrict__ pos_clip, Viewports vp, int V, int H, int W, TriTiles tt,
-                 const float *__restrict__ ipart, const float *__restrict__ rpart, Adjacency adj,
-                 const float *__restrict__ mvp, const int32_t *__restrict__ vert_view, float *__restrict__ grad_attr,
-                 float4 *__restrict__ grad_pos_clip, float *__restrict__ grad_pos) {
-    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t v = gid / GV_LANES;
-    const int lane = (int)(gid - v * GV_LANES);
-    const bool live = v < V;
-    float s[CC];
-#pragma unroll
-    for (int c = 0; c < CC; c++) s[c] = 0.0f;
-    float gx = 0.0f, gy = 0.0f, gw = 0.0f;
-    if (live) {
-        const int j0 = adj.offsets[v], j1 = adj.offsets[v + 1];
-        if (lane < 4) {
-            for (int j = j0 + lane; j < j1; j += 4) {
-                const int cr = adj.corners[j];
-                const int t = cr / 3, i = cr - 3 * t;
-                float a[CC];
-#pragma unroll
-                for (int c = 0; c < CC; c++) a[c] = 0.0f;
-                for (int e = tt.offsets[t]; e < tt.offsets[t + 1]; e++) {
-                    const int2 ent = tt.entries[e];
-                    const float *pp = ipart + ((int64_t)ent.x * DRESSI_TILE_PIX + ent.y) * 3 * CC + i * CC;
-#pragma unroll
-                    for (int c = 0; c < CC; c++) a[c] += pp[c];
-                }
-#pragma unroll
-                for (int c = 0; c < CC; c++) s[c] += a[c];
-            }
-        }
-        const float4 p = pos_clip[v];
-        const double iw = 1.0 / (double)p.w, xn = (double)(p.x / p.w), yn = (double)(p.y / p.w);
-        for (int j = j0 + lane; j < j1; j += GV_LANES) {
-            const int c = adj.corners[j];
-            const int t = c / 3, i = c - 3 * t;
-            // a triangle without fragments adds nothing (as in k_rast_bwd_vertex)
-            if (tt.offsets[t] == tt.offsets[t + 1]) continue;
-            double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-            for (int e = tt.offsets[t]; e < tt.offsets[t + 1]; e++) {
-                const int2 ent = tt.entries[e];
-                const float *r = rpart + ((int64_t)ent.x * DRESSI_TILE_PIX + ent.y) * 9 + 3 * i;
-                a0 += (double)r[0];
-                a1 += (double)r[1];
-                a2 += (double)r[2];
-            }
-            const int4 q = dr_viewport(vp, t, H, W);
-            const double hw = 0.5 * (double)q.z, hh = 0.5 * (double)q.w;
-            gx += (float)(a0 * hw * iw);
-            gy += (float)(-a1 * hh * iw);
-            gw += (float)((-a0 * hw * xn + a1 * hh * yn) * iw + a2);
-        }
-    }
-#pragma unroll
-    for (int c = 0; c < CC; c++) {
-#pragma unroll
-        for (int m = 1; m < 4; m <<= 1) s[c] += __shfl_xor(s[c], m, 64);
-    }
-#pragma unroll
-    for (int m = 1; m < GV_LANES; m <<= 1) {
-        gx += __shfl_xor(gx, m, 64);
-        gy += __shfl_xor(gy, m, 64);
-        gw += __shfl_xor(gw, m, 64);
-    }
-    if (!live || lane != 0) return;
-#pragma unroll
-    for (int c = 0; c < CC; c++) grad_attr[v * CC + c] = s[c];
-    const float4 q = make_float4(gx, gy, 0.0f, gw);
-    grad_pos_clip[v] = q;
-    const float *M = mvp + 16 * (int64_t)(vert_view ? vert_view[v] : 0);
-    float hx = 0.0f, hy = 0.0f, hz = 0.0f;
-    hx += M[0] * q.x + M[4] * q.y + M[8] * q.z + M[12] * q.w;
-    hy += M[1] * q.x + M[5] * q.y + M[9] * q.z + M[13] * q.w;
-    hz += M[2] * q.x + M[6] * q.y + M[10] * q.z + M[14] * q.w;
-    grad_pos[3 * v] = hx;
-    grad_pos[3 * v + 1] = hy;
-    grad_pos[3 * v + 2] = hz;
-}
-
 // Per tile (B = K = 1): the interpolation adjoint of every fragment (its
 // barycentric gradient and staged row, as k_interp_bwd_tile), then, from that
 // barycentric gradient, the rasterization adjoint of the same fragment (as
@@ -1717,14 +1628,17 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX) __attribute__((amdgpu_waves_p
     }
 }
 
-static size_t geometry_scratch(int H, int W, int Cv, Carver &c, size_t *o) {
+static size_t geometry_scratch(int H, int W, int V, int Cv, Carver &c, size_t *o) {
     const size_t n = (size_t)tiles_x(W) * tiles_y(H) * DRESSI_TILE_PIX;
-    o[0] = c.take(sizeof(float) * n * 3 * Cv);
-    o[1] = c.take(sizeof(float) * n * 9);
+    o[0] = c.take(sizeof(float) * n * 3 * Cv);   // per-tile interpolation records
+    o[1] = c.take(sizeof(float) * n * 9);        // per-tile rasterization records
+    o[2] = c.take(sizeof(float) * 3 * (size_t)V);   // transform adjoint
+    o[3] = c.take(sizeof(float) * 3 * (size_t)V);   // normal-sum adjoint
     return c.off;
 }
 
-extern "C" int dressi_geometry_bwd(dressi_ctx *ctx, const float *vattr, int V, int Cv, const int32_t *tris, int T,
+extern "C" int dressi_geometry_bwd(dressi_ctx *ctx, const float *pos, const float *vattr, int V, int Cv,
+                                   const int32_t *tris, int T,
                                    const float *pos_clip, const float *mvp, const int32_t *vert_view,
                                    const int32_t *tri_view, const int32_t *views, int n_views, int H, int W,
                                    int cull, const int32_t *tri_id, const float *bary, const float *grad_gbuf,
@@ -1742,16 +1656,17 @@ extern "C" int dressi_geometry_bwd(dressi_ctx *ctx, const float *vattr, int V, i
         if (rc) return rc;
     }
     if (V == 0) return DRESSI_OK;
-    if (!vattr || !tris || !pos_clip || !mvp || !tri_id || !bary || !grad_gbuf || !frag_index || !adj ||
+    if (!pos || !vattr || !tris || !pos_clip || !mvp || !tri_id || !bary || !grad_gbuf || !frag_index || !adj ||
         !grad_vattr || !grad_bary || !grad_pos_clip || !grad_pos)
         return dressi_fail(ctx, DRESSI_EINVAL, "geometry_bwd: null pointer");
     hipStream_t st = (hipStream_t)stream;
     Carver c;
-    size_t o[2];
-    geometry_scratch(H, W, Cv, c, o);
+    size_t o[4];
+    geometry_scratch(H, W, V, Cv, c, o);
     int rc = dressi_scratch(ctx, c.off, st);
     if (rc) return rc;
     float *ipart = at<float>(ctx->scratch, o[0]), *rpart = at<float>(ctx->scratch, o[1]);
+    float *gpos_t = at<float>(ctx->scratch, o[2]), *gacc = at<float>(ctx->scratch, o[3]);
     FragLists fl;
     TriTiles tt;
     dressi_fragindex_view(const_cast<void *>(frag_index), 1, 1, H, W, T, fl, tt);
@@ -1779,16 +1694,8 @@ extern "C" int dressi_geometry_bwd(dressi_ctx *ctx, const float *vattr, int V, i
             DR_LAUNCH("k_rast_bwd_tile", (k_rast_bwd_tile), nt, DRESSI_TILE_PIX, sizeof(float) * 9 * DRESSI_TILE_PIX,
                       st, pc4, tris, vp, V, T, H, W, 1, cull, 0, tri_id, fl, ntx, nt, gbo, nullptr, rpart);
     }
-    const Adjacency A = adjacency_view(adj, V);
-    const int g = (int)(((int64_t)V * GV_LANES + 255) / 256);
-    if (Cv == 6)
-        DR_LAUNCH("k_geo_vertex", (k_geo_vertex<6>), g, 256, 0, st, reinterpret_cast<const float4 *>(pos_clip), vp,
-                  V, H, W, tt, ipart, rpart, A, mvp, vert_view, grad_vattr, reinterpret_cast<float4 *>(grad_pos_clip),
-                  grad_pos);
-    else
-        DR_LAUNCH("k_geo_vertex", (k_geo_vertex<9>), g, 256, 0, st, reinterpret_cast<const float4 *>(pos_clip), vp,
-                  V, H, W, tt, ipart, rpart, A, mvp, vert_view, grad_vattr, reinterpret_cast<float4 *>(grad_pos_clip),
-                  grad_pos);
+    dr_geo_vertex(Cv, pos, tris, pos_clip, vp, V, H, W, tt, ipart, rpart, adjacency_view(adj, V), mvp, vert_view,
+                  grad_vattr, grad_pos_clip, gpos_t, gacc, grad_pos, st);
     return dressi_launch_check(ctx, "geometry_bwd");
 }
 
@@ -1816,8 +1723,8 @@ size_t dr_need_raster(const dressi_limits &l, int64_t cap) {
         // dressi_geometry_bwd (one image, single layer; attribute rows of up
         // to max(C, 9) channels)
         Carver c;
-        size_t o[2];
-        geometry_scratch(H, W, std::max(l.C, 9), c, o);
+        size_t o[4];
+        geometry_scratch(H, W, l.V, std::max(l.C, 9), c, o);
         need = std::max(need, c.off);
     }
     return std::max(need, dressi_fragindex_tmp_bytes(B, K, H, W, T));

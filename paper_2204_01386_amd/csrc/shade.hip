@@ -247,6 +247,137 @@ __global__ void k_vertex_attrs_bwd2(const float *__restrict__ pos, const int32_t
     grad_pos[3 * (int64_t)v + 2] = s.z;
 }
 
+// The per-vertex part of the geometry adjoint of one image (B = K = 1), eight
+// lanes per vertex.  Attribute gradient: lanes 0-3 take the corners j, j + 4,
+// ... and are combined as k_interp_bwd_vertex_c combines its four;
+// clip-space gradient: all eight take the corners j, j + 8, ... as
+// k_rast_bwd_vertex does; then the transform adjoint of k_transform_bwd, and
+// the first pass of the vertex-normal adjoint (k_vertex_attrs_bwd1: the
+// gradient of the un-normalised normal sum, recomputed over the same lanes).
+// Each corner's triangle's tile records are summed in tile order through the
+// triangle -> tile lists, so every value is summed over the same terms in
+// the same order as those kernels.
+#define GV_LANES 8
+static_assert(GV_LANES == VA_LANES, "the normal sums use the vertex-attribute lanes");
+template <int CC>
+__global__ void __launch_bounds__(256)
+    k_geo_vertex(const float *__restrict__ pos, const int32_t *__restrict__ tris, const float4 *__restrict__ pos_clip,
+                 Viewports vp, int V, int H, int W, TriTiles tt, const float *__restrict__ ipart,
+                 const float *__restrict__ rpart, Adjacency adj, const float *__restrict__ mvp,
+                 const int32_t *__restrict__ vert_view, float *__restrict__ grad_attr,
+                 float4 *__restrict__ grad_pos_clip, float *__restrict__ grad_pos_t, float *__restrict__ gacc) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t v = gid / GV_LANES;
+    const int lane = (int)(gid - v * GV_LANES);
+    const bool live = v < V;
+    float s[CC];
+#pragma unroll
+    for (int c = 0; c < CC; c++) s[c] = 0.0f;
+    float gx = 0.0f, gy = 0.0f, gw = 0.0f;
+    if (live) {
+        const int j0 = adj.offsets[v], j1 = adj.offsets[v + 1];
+        if (lane < 4) {
+            for (int j = j0 + lane; j < j1; j += 4) {
+                const int cr = adj.corners[j];
+                const int t = cr / 3, i = cr - 3 * t;
+                float a[CC];
+#pragma unroll
+                for (int c = 0; c < CC; c++) a[c] = 0.0f;
+                for (int e = tt.offsets[t]; e < tt.offsets[t + 1]; e++) {
+                    const int2 ent = tt.entries[e];
+                    const float *pp = ipart + ((int64_t)ent.x * DRESSI_TILE_PIX + ent.y) * 3 * CC + i * CC;
+#pragma unroll
+                    for (int c = 0; c < CC; c++) a[c] += pp[c];
+                }
+#pragma unroll
+                for (int c = 0; c < CC; c++) s[c] += a[c];
+            }
+        }
+        const float4 p = pos_clip[v];
+        const double iw = 1.0 / (double)p.w, xn = (double)(p.x / p.w), yn = (double)(p.y / p.w);
+        for (int j = j0 + lane; j < j1; j += GV_LANES) {
+            const int c = adj.corners[j];
+            const int t = c / 3, i = c - 3 * t;
+            // a triangle without fragments adds nothing (as in k_rast_bwd_vertex)
+            if (tt.offsets[t] == tt.offsets[t + 1]) continue;
+            double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+            for (int e = tt.offsets[t]; e < tt.offsets[t + 1]; e++) {
+                const int2 ent = tt.entries[e];
+                const float *r = rpart + ((int64_t)ent.x * DRESSI_TILE_PIX + ent.y) * 9 + 3 * i;
+                a0 += (double)r[0];
+                a1 += (double)r[1];
+                a2 += (double)r[2];
+            }
+            const int4 q = dr_viewport(vp, t, H, W);
+            const double hw = 0.5 * (double)q.z, hh = 0.5 * (double)q.w;
+            gx += (float)(a0 * hw * iw);
+            gy += (float)(-a1 * hh * iw);
+            gw += (float)((-a0 * hw * xn + a1 * hh * yn) * iw + a2);
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < CC; c++) {
+#pragma unroll
+        for (int m = 1; m < 4; m <<= 1) s[c] += __shfl_xor(s[c], m, 64);
+    }
+#pragma unroll
+    for (int m = 1; m < GV_LANES; m <<= 1) {
+        gx += __shfl_xor(gx, m, 64);
+        gy += __shfl_xor(gy, m, 64);
+        gw += __shfl_xor(gw, m, 64);
+    }
+    const dbl3 nacc = vertex_acc(pos, tris, adj, (int)v, V, live, lane);
+    if (!live || lane != 0) return;
+#pragma unroll
+    for (int c = 0; c < CC; c++) grad_attr[v * CC + c] = s[c];
+    const float4 q = make_float4(gx, gy, 0.0f, gw);
+    grad_pos_clip[v] = q;
+    const float *M = mvp + 16 * (int64_t)(vert_view ? vert_view[v] : 0);
+    float hx = 0.0f, hy = 0.0f, hz = 0.0f;
+    hx += M[0] * q.x + M[4] * q.y + M[8] * q.z + M[12] * q.w;
+    hy += M[1] * q.x + M[5] * q.y + M[9] * q.z + M[13] * q.w;
+    hz += M[2] * q.x + M[6] * q.y + M[10] * q.z + M[14] * q.w;
+    grad_pos_t[3 * v] = hx;
+    grad_pos_t[3 * v + 1] = hy;
+    grad_pos_t[3 * v + 2] = hz;
+    // (g - (g.n) n) / |a| with n = a / |a|, g the normal's gradient
+    const double l = sqrt(nacc.x * nacc.x + nacc.y * nacc.y + nacc.z * nacc.z);
+    double rx = 0.0, ry = 0.0, rz = 0.0;
+    if (l > 0.0) {
+        const double il = 1.0 / l;
+        const double nx = nacc.x * il, ny = nacc.y * il, nz = nacc.z * il;
+        const double ggx = s[0], ggy = s[1], ggz = s[2];
+        const double gn = ggx * nx + ggy * ny + ggz * nz;
+        rx = (ggx - gn * nx) * il;
+        ry = (ggy - gn * ny) * il;
+        rz = (ggz - gn * nz) * il;
+    }
+    gacc[3 * v] = (float)rx;
+    gacc[3 * v + 1] = (float)ry;
+    gacc[3 * v + 2] = (float)rz;
+}
+
+// The per-vertex kernel above, then the second pass of the vertex-normal
+// adjoint (k_vertex_attrs_bwd2): the world-position gradient.
+void dr_geo_vertex(int Cv, const float *pos, const int32_t *tris, const float *pos_clip, Viewports vp, int V, int H,
+                   int W, TriTiles tt, const float *ipart, const float *rpart, Adjacency adj, const float *mvp,
+                   const int32_t *vert_view, float *grad_attr, float *grad_pos_clip, float *grad_pos_t, float *gacc,
+                   float *grad_pos, hipStream_t st) {
+    const int g = (int)(((int64_t)V * GV_LANES + 255) / 256);
+    const float4 *pc4 = reinterpret_cast<const float4 *>(pos_clip);
+    float4 *gpc = reinterpret_cast<float4 *>(grad_pos_clip);
+    if (Cv == 6)
+        DR_LAUNCH("k_geo_vertex", (k_geo_vertex<6>), g, 256, 0, st, pos, tris, pc4, vp, V, H, W, tt, ipart, rpart,
+                  adj, mvp, vert_view, grad_attr, gpc, grad_pos_t, gacc);
+    else
+        DR_LAUNCH("k_geo_vertex", (k_geo_vertex<9>), g, 256, 0, st, pos, tris, pc4, vp, V, H, W, tt, ipart, rpart,
+                  adj, mvp, vert_view, grad_attr, gpc, grad_pos_t, gacc);
+    const int nb = (int)(((int64_t)V * VA_LANES + 255) / 256);
+    DR_LAUNCH("k_vertex_attrs_bwd2", (k_vertex_attrs_bwd2), nb, 256, 0, st, pos, tris, adj, V, Cv, grad_attr,
+              grad_pos_t, gacc, grad_pos);
+}
+
+
 extern "C" int dressi_vertex_attrs(dressi_ctx *ctx, const float *pos, const int32_t *tris, int V, int T,
                                    const float *extra, const int32_t *adj, float *out, void *stream) {
     if (!ctx) return DRESSI_EINVAL;

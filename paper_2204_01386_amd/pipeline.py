@@ -451,14 +451,11 @@ class Step(_TwoStreams):
                        "texture_grad_invuv", "texel")
             gb_in = self.g_bary_uv
         if self.packed_geo:
-            ck(_lib.dressi_geometry_bwd(h, _p(self.vattr), self.V, self.Cv, _p(self.tris), self.T, _p(self.pos_clip),
-                                        _p(self.mvp), None, None, None, 0, H, W, 0, _p(self.tri_id), _p(self.bary),
-                                        _p(self.g_gbuf), _p(gb_in), _p(self.frag_index), _p(self.adj),
-                                        _p(self.g_vattr), _p(self.g_bary), _p(self.g_clip), _p(self.g_pos_t), s),
-               "geometry_bwd")
-            ck(_lib.dressi_vertex_attrs_bwd(h, _p(self.pos), _p(self.tris), self.V, self.T, self.Cv, _p(self.adj),
-                                            _p(self.g_vattr), _p(self.g_pos_t), _p(self.g_pos), s),
-               "vertex_attrs_bwd")
+            ck(_lib.dressi_geometry_bwd(h, _p(self.pos), _p(self.vattr), self.V, self.Cv, _p(self.tris), self.T,
+                                        _p(self.pos_clip), _p(self.mvp), None, None, None, 0, H, W, 0,
+                                        _p(self.tri_id), _p(self.bary), _p(self.g_gbuf), _p(gb_in),
+                                        _p(self.frag_index), _p(self.adj), _p(self.g_vattr), _p(self.g_bary),
+                                        _p(self.g_clip), _p(self.g_pos), s), "geometry_bwd")
         else:
             self._backward_geometry(gb_in)
         self._join()
@@ -919,13 +916,11 @@ class BatchStep(_TwoStreams):
                                                   _p(self.g_tex), self._sa("texel")), "texture_grad_invuv", "texel")
         ck = self._chk
         V, T = self.V, self.T
-        ck(_lib.dressi_geometry_bwd(h, _p(self.vattr), V, 6, _p(self.tris), T, _p(self.pos_clip), _p(self.mvp),
-                                    _p(self.vert_view), _p(self.tri_view), _p(self.views), self.n, H, W, 0,
-                                    _p(self.tri_id), _p(self.bary), _p(self.g_gbuf), _p(self.g_bary_uv),
+        ck(_lib.dressi_geometry_bwd(h, _p(self.pos), _p(self.vattr), V, 6, _p(self.tris), T, _p(self.pos_clip),
+                                    _p(self.mvp), _p(self.vert_view), _p(self.tri_view), _p(self.views), self.n, H,
+                                    W, 0, _p(self.tri_id), _p(self.bary), _p(self.g_gbuf), _p(self.g_bary_uv),
                                     _p(self.frag_index), _p(self.adj), _p(self.g_vattr), _p(self.g_bary),
-                                    _p(self.g_clip), _p(self.g_pos_t), st), "geometry_bwd")
-        ck(_lib.dressi_vertex_attrs_bwd(h, _p(self.pos), _p(self.tris), V, T, 6, _p(self.adj), _p(self.g_vattr),
-                                        _p(self.g_pos_t), _p(self.g_pos), st), "vertex_attrs_bwd")
+                                    _p(self.g_clip), _p(self.g_pos), st), "geometry_bwd")
         self._join()
 
     def _backward_geometry(self):
