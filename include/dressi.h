@@ -346,6 +346,18 @@ int dressi_invuv_build(dressi_ctx *ctx, const dressi_tex_desc *td, const float *
 int dressi_texture_grad_invuv(dressi_ctx *ctx, const dressi_tex_desc *td, const float *coord,
                               const int32_t *tri_id, int S, int H, int W, const int32_t *inv,
                               const float *grad_out, float *grad_tex, void *stream);
+/* The same gather (Algorithm 1's gathering pass, §3.3.2) from per-pixel
+ * records instead of coordinates and gradients: rec [S, H*W] of 32 bytes
+ * each, 16-byte aligned, as dressi_packed_backward writes them beside its
+ * registrations in inv (a registered pixel's bilinear taps, packed as
+ * x0 | x1 << 16 and y0 | y1 << 16, its fractions fx, fy, then the gradient
+ * of its RGBA sample).  A kept pixel costs one 32-byte read and no tap
+ * arithmetic; the sums are bitwise those of dressi_texture_grad_invuv on the
+ * same map.  2-D RGBA textures and texture arrays (Ct = 4), grad_tex 16-byte
+ * aligned; repeat wrap needs Ht, Wt >= 3 (DRESSI_EINVAL otherwise).  Only the
+ * records of pixels registered in inv are read. */
+int dressi_texture_grad_invrec(dressi_ctx *ctx, const dressi_tex_desc *td, int S, int H, int W,
+                               const int32_t *inv, const void *rec, float *grad_tex, void *stream);
 
 /* ----------------------------------------------------------------------------
  * HardSoftRas blend (§3.4.3, BuildBlend):
@@ -535,14 +547,18 @@ int dressi_packed_forward(dressi_ctx *ctx, const dressi_packed_scene *scene, con
  * fed to dressi_interpolate_bwd of uv), and, when inv is given (as set by
  * dressi_packed_forward), every covered pixel registered in it as
  * dressi_invuv_build does: dressi_texture_grad_invuv then gives the texture
- * gradient.  Inputs are the forward's outputs.  Phong: grad_gbuf and
+ * gradient.  inv_rec (Phong, nullable; [B, H*W] records of 32 bytes,
+ * 16-byte aligned): the record of every covered pixel that a map registers
+ * (here in inv, or earlier by dressi_invuv_build on the same coordinates)
+ * for dressi_texture_grad_invrec, the faster gather; other entries are
+ * left as they were.  Inputs are the forward's outputs.  Phong: grad_gbuf and
  * grad_bary_uv may be NULL (only the albedo sample's gradient, as a
  * texture-only step needs). */
 int dressi_packed_backward(dressi_ctx *ctx, const dressi_packed_scene *scene, const int32_t *tri_id, int B,
                            int H, int W, const float *gbuf, const float *uvbuf, const float *samp,
                            const float *color, const float *sil, const float *target, const float *weight,
                            float *loss, float *grad_color, float *grad_sil, float *grad_gbuf,
-                           float *grad_samp, float *grad_bary_uv, int32_t *inv, void *stream);
+                           float *grad_samp, float *grad_bary_uv, int32_t *inv, void *inv_rec, void *stream);
 
 /* Geometry adjoints of one image (B = 1, K = 1, hard: after the packed
  * pass), in three launches: the same values as dressi_interpolate_bwd of

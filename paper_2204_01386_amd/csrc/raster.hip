@@ -227,6 +227,10 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX)
     const float dscale = (float)W * 256.0f;
     const TriSetup *sv = setup + (int64_t)b * T;
     const int32_t *bin = bins + (int64_t)bt * cap;
+    // the bin's first entries are read beside its count, not after it (in
+    // bounds whatever the count: the bin has `cap` slots; entries past the
+    // count are never used), one dependent load fewer
+    const int t_first = p < cap ? bin[p] : -1;
     int nbin = counts[bt];
     if (nbin > cap) nbin = cap;
 
@@ -239,7 +243,7 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX)
         __syncthreads();
         for (int c0 = 0; c0 < nbin; c0 += DRESSI_TILE_PIX) {
             if (c0 + p < nbin) {
-                int t = bin[c0 + p];
+                int t = c0 == 0 ? t_first : bin[c0 + p];
                 TriSetup s = sv[t];
                 raster_tri_in_tile<SOFT>(s, t, tx, ty, r, dscale, slot, prev);
             }
@@ -577,6 +581,8 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX) __attribute__((amdgpu_waves_p
     const int wy1 = wy0 + 64 / DRESSI_TILE - 1;
     const int px0 = DRESSI_SUBPIX * wx0 + DRESSI_SUBPIX / 2;                 // tile's first pixel centre
     const int py0 = DRESSI_SUBPIX * (ty * DRESSI_TILE) + DRESSI_SUBPIX / 2;
+    // the first batch of the bin is read beside its count (as in k_raster)
+    const int t_first = p < cap ? bin[p] : -1;
     int nbin = counts[bt];
     if (nbin > cap) nbin = cap;
     bool inE = true;   // this lane's pixel is in the edge mask (the second banded pass)
@@ -619,7 +625,7 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX) __attribute__((amdgpu_waves_p
                     // whose vertex box misses this tile is marked far away
                     // (never wanted by the covering walk) without loading
                     // the rest of its record
-                    const int2 hb = *reinterpret_cast<const int2 *>(&sv[bin[c0 + p]].hbox0);
+                    const int2 hb = *reinterpret_cast<const int2 *>(&sv[c0 == 0 ? t_first : bin[c0 + p]].hbox0);
                     const int ty0 = ty * DRESSI_TILE, ty1 = ty0 + DRESSI_TILE - 1;
                     if (hi16(hb.x) < wx0 || lo16(hb.x) > wx1 || hi16(hb.y) < ty0 || lo16(hb.y) > ty1) {
                         shb[p] = make_int2((int)0x80008000u, (int)0x80008000u);
@@ -629,7 +635,7 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX) __attribute__((amdgpu_waves_p
                     }
                 }
                 if (stage) {
-                    const int t = bin[c0 + p];
+                    const int t = c0 == 0 ? t_first : bin[c0 + p];
                     const TriSetup s = sv[t];
                     // 32-bit integer path: every pixel-to-vertex difference over the
                     // tile and every edge vector below 2^15 in magnitude

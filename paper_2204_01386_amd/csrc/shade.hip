@@ -980,8 +980,8 @@ __global__ void __launch_bounds__(256)
                  const float *__restrict__ color, const float *__restrict__ sil, const float4 *__restrict__ target,
                  const float *__restrict__ weight, float w_uniform, float *__restrict__ grad_color,
                  float *__restrict__ grad_sil, float *__restrict__ g_gbuf, float *__restrict__ g_samp,
-                 float2 *__restrict__ g_bary_uv, int32_t *__restrict__ inv, float *__restrict__ partial,
-                 int skip_empty) {
+                 float2 *__restrict__ g_bary_uv, int32_t *__restrict__ inv, int4 *__restrict__ rec,
+                 float *__restrict__ partial, int skip_empty) {
     __shared__ float red[256];
     float acc = 0.0f;
     // one pixel per lane (grid-stride when the image has more pixels than the
@@ -1033,7 +1033,7 @@ __global__ void __launch_bounds__(256)
             gr.albedo = TEX ? g_samp : (g_gbuf ? g_gbuf + 6 : nullptr);
             gr.albedo_stride = TEX ? 4 : CV;
             shade_bwd_frag(mode, in, s, d3{g0, g1, g2}, nullptr, gr, i, g_gbuf != nullptr);
-            if (TEX && (inv || g_bary_uv)) {
+            if (TEX && (inv || g_bary_uv || rec)) {
                 const float q[2] = {uvbuf[2 * i], uvbuf[2 * i + 1]};
                 const Taps tp = make_taps(sc.td, q, tex_layer(sc.td, tri_id, i));
                 float du = 0.0f, dv = 0.0f;
@@ -1045,10 +1045,11 @@ __global__ void __launch_bounds__(256)
                     atomicMax(&inv[sl * cells + ((int64_t)tp.face * sc.td.Ht + cy) * sc.td.Wt + cx],
                               (int)(i - sl * npix));
                 }
-                if (tp.ok && g_bary_uv) {
+                if (tp.ok && (g_bary_uv || rec)) {
                     float gs[4];
                     ldv<4>(g_samp + 4 * i, gs, 4);
-                    tex_dcoord<4>(sc.tex, sc.td, tp, gs, 4, du, dv);
+                    if (g_bary_uv) tex_dcoord<4>(sc.tex, sc.td, tp, gs, 4, du, dv);
+                    if (rec) invrec_put(rec + 2 * i, tp, gs);
                 }
                 // barycentric adjoint of the interpolated coordinate
                 float2 gb = make_float2(0.0f, 0.0f);
@@ -1142,13 +1143,15 @@ extern "C" int dressi_packed_backward(dressi_ctx *ctx, const dressi_packed_scene
                                       const float *samp, const float *color, const float *sil,
                                       const float *target, const float *weight, float *loss, float *grad_color,
                                       float *grad_sil, float *grad_gbuf, float *grad_samp, float *grad_bary_uv,
-                                      int32_t *inv, void *stream) {
+                                      int32_t *inv, void *inv_rec, void *stream) {
     int rc = check_packed(ctx, sc, B, H, W, "packed_backward");
     if (rc) return rc;
     const int64_t npix = (int64_t)H * W, n = (int64_t)B * npix;
     const bool tex = sc->mode == DRESSI_SHADE_PHONG;
     if (!loss) return dressi_fail(ctx, DRESSI_EINVAL, "packed_backward: null loss");
     if (inv && !tex) return dressi_fail(ctx, DRESSI_EINVAL, "packed_backward: inv is for the textured (Phong) pass");
+    if (inv_rec && (!tex || !al16(inv_rec)))
+        return dressi_fail(ctx, DRESSI_EINVAL, "packed_backward: inv_rec is for the textured pass, 16-byte aligned");
     if (n > 0 && (!tri_id || !gbuf || !color || !sil || !target || (!tex && !grad_gbuf) ||
                   (tex && (!uvbuf || !samp || !grad_samp))))
         return dressi_fail(ctx, DRESSI_EINVAL, "packed_backward: null input or output");
@@ -1167,12 +1170,12 @@ extern "C" int dressi_packed_backward(dressi_ctx *ctx, const dressi_packed_scene
         dressi_fill_f32(partial, 0.0f, 1, st);
     } else if (tex) {
         DR_LAUNCH("k_packed_bwd", (k_packed_bwd<6, true>), (int)nb, 256, 0, st, sc->mode, *sc, tri_id, npix, n, gbuf,
-                  uvbuf, samp, color, sil, t4, weight, w, grad_color, grad_sil, grad_gbuf, grad_samp, gb, inv, partial,
-                  ctx->skip_empty);
+                  uvbuf, samp, color, sil, t4, weight, w, grad_color, grad_sil, grad_gbuf, grad_samp, gb, inv,
+                  static_cast<int4 *>(inv_rec), partial, ctx->skip_empty);
     } else {
         DR_LAUNCH("k_packed_bwd", (k_packed_bwd<9, false>), (int)nb, 256, 0, st, sc->mode, *sc, tri_id, npix, n,
-                  gbuf, uvbuf, samp, color, sil, t4, weight, w, grad_color, grad_sil, grad_gbuf, grad_samp, gb, inv, partial,
-                  ctx->skip_empty);
+                  gbuf, uvbuf, samp, color, sil, t4, weight, w, grad_color, grad_sil, grad_gbuf, grad_samp, gb, inv,
+                  nullptr, partial, ctx->skip_empty);
     }
     DR_LAUNCH("k_loss_sum", (k_loss_sum), 1, LOSS_BS, 0, st, partial, (int)nb, weight ? 1.0f : w, loss);
     return dressi_launch_check(ctx, "packed_backward");

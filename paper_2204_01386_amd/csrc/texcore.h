@@ -102,6 +102,15 @@ __device__ __forceinline__ Taps make_taps(const dressi_tex_desc &td, const float
     return t;
 }
 
+// Record of a registered pixel for the inverse-UV gather of an RGBA texture
+// (32 bytes): its taps packed as x0 | x1 << 16 and y0 | y1 << 16 and its
+// bilinear fractions, then the gradient of its sample.  The gather reads a
+// kept pixel's record instead of its coordinate and gradient.
+__device__ __forceinline__ void invrec_put(int4 *__restrict__ r, const Taps &t, const float *g) {
+    r[0] = make_int4(t.x0 | (t.x1 << 16), t.y0 | (t.y1 << 16), __float_as_int(t.fx), __float_as_int(t.fy));
+    r[1] = make_int4(__float_as_int(g[0]), __float_as_int(g[1]), __float_as_int(g[2]), __float_as_int(g[3]));
+}
+
 // CT channels per texel or pixel (CT = 0: Ct at run time, at most 16).
 // Multiples of 4 are moved as float4 (16-byte aligned rows).
 template <int CT>

@@ -232,6 +232,15 @@ static Jitter jitter_of_frame(uint32_t frame) {
 // f has its taps on f, so they are recomputed from its coordinate alone.
 // More rows per lane (R) means fewer, larger blocks: more loads in flight per
 // lane and fewer halo cells per texel, against more LDS per block.
+// c modulo n in [0, n): one addition or subtraction for the halo's usual
+// range, a division only for blocks that reach past a small texture
+__device__ __forceinline__ int wrap_repeat(int c, int n) {
+    if (c >= 0 && c < n) return c;
+    if (c < 0 && c >= -n) return c + n;
+    if (c >= n && c < 2 * n) return c - n;
+    return ((c % n) + n) % n;
+}
+
 template <int SG, int R>
 struct IvGeom {
     static constexpr int NT = 256;                 // lanes: 16 columns x 16 rows
@@ -240,11 +249,16 @@ struct IvGeom {
     static constexpr int PT = (HN + NT - 1) / NT;  // halo cells per lane
 };
 
-template <int CT, int SG, int R>
+// With REC (RGBA, 2-D or array textures) each kept pixel's taps, fractions
+// and gradient come from its record (invrec_put) in one 32-byte read, in
+// place of its coordinate and gradient: the same values.
+template <int CT, int SG, int R, bool REC = false>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(((R == 1 && CT == 8) || (R == 2 && CT > 0 && CT <= 4)) ? 8 : 1)))
     k_invuv_gather(dressi_tex_desc td, const float *__restrict__ coord, const int32_t *__restrict__ tri_id,
                    int64_t npix, int S, int nsplit, const int32_t *__restrict__ inv,
-                   const float *__restrict__ grad_out, float *__restrict__ out, int xcd) {
+                   const float *__restrict__ grad_out, float *__restrict__ out, int xcd,
+                   const int4 *__restrict__ rec) {
+    static_assert(!REC || CT == 4, "records hold an RGBA gradient");
     // per halo cell of each slice of the group: the winner's four tap
     // coordinates, bilinear fractions (fx < 0: no winner, or one on another
     // cube face) and pixel gradient
@@ -262,14 +276,25 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(((R ==
     // workgroups of neighbouring texel blocks share inverse-UV cells and their
     // winners' pixel rows: with `xcd`, each XCD takes one contiguous range of
     // the grid (rows of blocks), so they are fetched into one L2
-    const int64_t gxy = (int64_t)gridDim.x * gridDim.y;
-    const int64_t lin = ((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-    const int64_t lb = xcd ? xcd_block(lin, gxy * gridDim.z) : lin;
-    const int bz = (int)(lb / gxy), byi = (int)((lb - bz * gxy) / gridDim.x);
-    const int bxi = (int)(lb - bz * gxy - (int64_t)byi * gridDim.x);
-    const int f = bz / nsplit, part = bz - f * nsplit;
-    const int per = (S + nsplit - 1) / nsplit;
-    const int s0 = part * per, s1 = min(S, s0 + per);
+    // (the divisions stay off the common path: with many short workgroups
+    // the scalar unit's division sequences cost more than their loads)
+    int bxi = blockIdx.x, byi = blockIdx.y, bz = blockIdx.z;
+    if (xcd) {
+        const int64_t gxy = (int64_t)gridDim.x * gridDim.y;
+        const int64_t lin = ((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+        const int64_t lb = xcd_block(lin, gxy * gridDim.z);
+        bz = (int)(lb / gxy);
+        byi = (int)((lb - bz * gxy) / gridDim.x);
+        bxi = (int)(lb - bz * gxy - (int64_t)byi * gridDim.x);
+    }
+    int f = bz, part = 0, s0 = 0, s1 = S;
+    if (nsplit > 1) {
+        f = bz / nsplit;
+        part = bz - f * nsplit;
+        const int per = (S + nsplit - 1) / nsplit;
+        s0 = part * per;
+        s1 = min(S, s0 + per);
+    }
     const int bx0 = bxi * IV_T, by0 = byi * G::TY;
     const int lx = threadIdx.x % IV_T, ly = threadIdx.x / IV_T;
     const int tx = bx0 + lx;
@@ -284,9 +309,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(((R ==
         if (h < G::HN) {
             int cy = by0 - 1 + h / G::HW, cx = bx0 - 1 + h % G::HW;
             bool ok = true;
-            if (wv == DRESSI_WRAP_REPEAT) cy = ((cy % Ht) + Ht) % Ht;
+            if (wv == DRESSI_WRAP_REPEAT) cy = wrap_repeat(cy, Ht);
             else ok = cy >= 0 && cy < Ht;
-            if (wu == DRESSI_WRAP_REPEAT) cx = ((cx % Wt) + Wt) % Wt;
+            if (wu == DRESSI_WRAP_REPEAT) cx = wrap_repeat(cx, Wt);
             else ok = ok && cx >= 0 && cx < Wt;
             if (ok) hoff[k] = cy * Wt + cx;
         }
@@ -318,6 +343,24 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(((R ==
             for (int k = 0; k < G::PT; k++) wpix[q][k] = wnext[q][k];
         if (g0 + SG < s1) load_group(g0 + SG, wnext);
         int found = 0;
+        // records: the first HK halo entries' loads are all in flight before
+        // the first is stored (all of them with one row per lane, two with
+        // more rows, where holding a third would spill registers)
+        constexpr int HK = REC ? (R == 1 ? G::PT : (G::PT < 2 ? G::PT : 2)) : 0;
+        int4 ra[SG][HK > 0 ? HK : 1], rb[SG][HK > 0 ? HK : 1];
+#pragma unroll
+        for (int q = 0; q < SG; q++)
+#pragma unroll
+            for (int k = 0; k < HK; k++) {
+                const int i = wpix[q][k];
+                ra[q][k] = make_int4(0, 0, -1, 0);
+                rb[q][k] = make_int4(0, 0, 0, 0);
+                if (i >= 0) {
+                    const int4 *rp = rec + 2 * ((int64_t)(g0 + q) * npix + i);
+                    ra[q][k] = rp[0];
+                    rb[q][k] = rp[1];
+                }
+            }
         // each winner's taps, computed once for the up to 9 texels that visit it
 #pragma unroll
         for (int q = 0; q < SG; q++) {
@@ -328,7 +371,25 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(((R ==
                 const int i = wpix[q][k];
                 int2 tp = make_int2(0, 0);
                 float2 fr = make_float2(-1.0f, 0.0f);
-                if (i >= 0) {
+                if (REC && i >= 0) {
+                    // a kept pixel's taps are on the face or layer of its cell
+                    int4 a, b;
+                    if (k < HK) {
+                        a = ra[q][k < HK ? k : 0];
+                        b = rb[q][k < HK ? k : 0];
+                    } else {
+                        const int4 *rp = rec + 2 * ((int64_t)(g0 + q) * npix + i);
+                        a = rp[0];
+                        b = rp[1];
+                    }
+                    tp = make_int2(a.x, a.y);
+                    fr = make_float2(__int_as_float(a.z), __int_as_float(a.w));
+                    found = 1;
+                    cg[q][h * NC] = __int_as_float(b.x);
+                    cg[q][h * NC + 1] = __int_as_float(b.y);
+                    cg[q][h * NC + 2] = __int_as_float(b.z);
+                    cg[q][h * NC + 3] = __int_as_float(b.w);
+                } else if (!REC && i >= 0) {
                     const int64_t o = (int64_t)(g0 + q) * npix + i;
                     // the winner's gradient is read alongside its coordinate
                     float g[NC];
@@ -402,20 +463,23 @@ __global__ void k_invuv_reduce(const float *__restrict__ part, int nsplit, int64
 template <int SG, int R>
 static void launch_gather_r(int ct, dim3 g, hipStream_t st, const dressi_tex_desc &td, const float *coord,
                             const int32_t *tri_id, int64_t npix, int S, int nsplit, const int32_t *inv,
-                            const float *grad_out, float *dst, int xcd) {
+                            const float *grad_out, float *dst, int xcd, const int4 *rec) {
     constexpr int nt = IvGeom<SG, R>::NT;
-    if (ct == 4)
+    if (rec)
+        DR_LAUNCH("k_invuv_gather", (k_invuv_gather<4, SG, R, true>), g, nt, 0, st, td, coord, tri_id, npix, S,
+                  nsplit, inv, grad_out, dst, xcd, rec);
+    else if (ct == 4)
         DR_LAUNCH("k_invuv_gather", (k_invuv_gather<4, SG, R>), g, nt, 0, st, td, coord, tri_id, npix, S,
-                  nsplit, inv, grad_out, dst, xcd);
+                  nsplit, inv, grad_out, dst, xcd, rec);
     else if (ct == 3)
         DR_LAUNCH("k_invuv_gather", (k_invuv_gather<3, SG, R>), g, nt, 0, st, td, coord, tri_id, npix, S,
-                  nsplit, inv, grad_out, dst, xcd);
+                  nsplit, inv, grad_out, dst, xcd, rec);
     else if (ct == 8)
         DR_LAUNCH("k_invuv_gather", (k_invuv_gather<8, SG, R>), g, nt, 0, st, td, coord, tri_id, npix, S,
-                  nsplit, inv, grad_out, dst, xcd);
+                  nsplit, inv, grad_out, dst, xcd, rec);
     else
         DR_LAUNCH("k_invuv_gather", (k_invuv_gather<0, SG, 1>), g, nt, 0, st, td, coord, tri_id, npix, S,
-                  nsplit, inv, grad_out, dst, xcd);
+                  nsplit, inv, grad_out, dst, xcd, rec);
 }
 
 // Large textures take the XCD-contiguous block order and two texel rows per
@@ -427,24 +491,29 @@ static void launch_gather_r(int ct, dim3 g, hipStream_t st, const dressi_tex_des
 // the loop over slices prefers more, smaller blocks in flight; a 4096^2
 // texture prefers the larger blocks again).  Any choice gives the same sums
 // in the same order.
-static int gather_rows(int rows, int ct, int S, const dressi_tex_desc &td) {
+static int gather_rows(int rows, int ct, int S, const dressi_tex_desc &td, bool rec) {
     if (ct != 3 && ct != 4 && ct != 8) return 1;
     if (rows == 1 || rows == 2 || rows == 4) return rows;
-    return (S == 1 || (int64_t)td.Ht * td.Wt >= IV_LARGE_CELLS) ? 2 : 1;
+    if ((int64_t)td.Ht * td.Wt >= IV_LARGE_CELLS) return 2;
+    return (S == 1 && !rec) ? 2 : 1;
 }
 
 static void launch_gather(int rows, int ct, int64_t gx, int64_t ty_cells, int gz, hipStream_t st,
                           const dressi_tex_desc &td, const float *coord, const int32_t *tri_id, int64_t npix,
-                          int S, int nsplit, const int32_t *inv, const float *grad_out, float *dst) {
-    const int R = gather_rows(rows, ct, S, td);
+                          int S, int nsplit, const int32_t *inv, const float *grad_out, float *dst,
+                          const int4 *rec) {
+    const int R = gather_rows(rows, ct, S, td, rec != nullptr);
     const int xcd = (int64_t)td.Ht * td.Wt >= IV_LARGE_CELLS;
     dim3 g((unsigned)gx, (unsigned)((ty_cells + 16 * R - 1) / (16 * R)), (unsigned)gz);
     if (R == 4)
-        launch_gather_r<DRESSI_IV_SG, 4>(ct, g, st, td, coord, tri_id, npix, S, nsplit, inv, grad_out, dst, xcd);
+        launch_gather_r<DRESSI_IV_SG, 4>(ct, g, st, td, coord, tri_id, npix, S, nsplit, inv, grad_out, dst, xcd,
+                                          rec);
     else if (R == 2)
-        launch_gather_r<DRESSI_IV_SG, 2>(ct, g, st, td, coord, tri_id, npix, S, nsplit, inv, grad_out, dst, xcd);
+        launch_gather_r<DRESSI_IV_SG, 2>(ct, g, st, td, coord, tri_id, npix, S, nsplit, inv, grad_out, dst, xcd,
+                                          rec);
     else
-        launch_gather_r<DRESSI_IV_SG, 1>(ct, g, st, td, coord, tri_id, npix, S, nsplit, inv, grad_out, dst, xcd);
+        launch_gather_r<DRESSI_IV_SG, 1>(ct, g, st, td, coord, tri_id, npix, S, nsplit, inv, grad_out, dst, xcd,
+                                          rec);
 }
 
 // float4 rows need 16-byte aligned bases
@@ -522,13 +591,13 @@ static void tex_bwd_pixels(const float *tex, const dressi_tex_desc &td, const fl
 // grid as well and the parts summed afterwards in `part`.
 static void tex_gather(const dressi_tex_desc &td, const float *coord, const int32_t *tri_id, int64_t npix,
                        int S, const int32_t *inv, const float *grad_out, float *part, float *grad_tex,
-                       hipStream_t st, int rows) {
+                       hipStream_t st, int rows, const int4 *rec = nullptr) {
     const int64_t cells = (int64_t)tex_faces(td) * td.Ht * td.Wt;
     const int nsplit = dressi_invuv_nsplit(cells, S);
     float *dst = nsplit > 1 ? part : grad_tex;
-    const int ct = aligned16(grad_out, dst) ? td.Ct : 0;
+    const int ct = rec ? 4 : (aligned16(grad_out, dst) ? td.Ct : 0);
     launch_gather(rows, ct, (td.Wt + IV_T - 1) / IV_T, td.Ht, tex_faces(td) * nsplit, st, td, coord, tri_id,
-                  npix, S, nsplit, inv, grad_out, dst);
+                  npix, S, nsplit, inv, grad_out, dst, rec);
     if (nsplit > 1) {
         int64_t ne = cells * td.Ct;
         DR_LAUNCH("k_invuv_reduce", (k_invuv_reduce), (int)((ne + 255) / 256), 256, 0, st, part, nsplit, ne,
@@ -641,7 +710,30 @@ extern "C" int dressi_texture_grad_invuv(dressi_ctx *ctx, const dressi_tex_desc 
     return dressi_launch_check(ctx, "texture_grad_invuv");
 }
 
-// texture_bwd (with jitter when asked) and texture_grad_invuv
+extern "C" int dressi_texture_grad_invrec(dressi_ctx *ctx, const dressi_tex_desc *td, int S, int H, int W,
+                                          const int32_t *inv, const void *rec, float *grad_tex, void *stream) {
+    // the records stand in for the texels, coordinates and triangle ids in the shared checks
+    int rc = check_tex(ctx, rec, td, rec, rec, S, H, W);
+    if (rc) return rc;
+    if ((rc = check_grad_tex(ctx, td, inv, "texture_grad_invrec: null inv"))) return rc;
+    if (td->kind == DRESSI_TEX_CUBE || td->Ct != 4)
+        return dressi_fail(ctx, DRESSI_EINVAL, "texture_grad_invrec: records are for 2-D RGBA textures and arrays");
+    if (!grad_tex || !aligned16(rec, grad_tex))
+        return dressi_fail(ctx, DRESSI_EINVAL, "texture_grad_invrec: rec and grad_tex must be 16-byte aligned");
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t cells = (int64_t)tex_faces(*td) * td->Ht * td->Wt;
+    float *part = nullptr;
+    const size_t pb = dressi_invuv_part_bytes(cells, td->Ct, S);
+    if (pb) {
+        if ((rc = dressi_scratch(ctx, pb, st))) return rc;
+        part = at<float>(ctx->scratch, 0);
+    }
+    tex_gather(*td, nullptr, nullptr, (int64_t)H * W, S, inv, nullptr, part, grad_tex, st, ctx->iv_rows,
+               static_cast<const int4 *>(rec));
+    return dressi_launch_check(ctx, "texture_grad_invrec");
+}
+
+// texture_bwd (with jitter when asked), texture_grad_invuv and _invrec
 size_t dr_need_texture(const dressi_limits &l) {
     if (l.tex_cells <= 0 || l.tex_channels <= 0) return 0;
     const int S = std::max(l.tex_slices, 1);

@@ -71,6 +71,11 @@ class _TwoStreams:
     # every consumer in a step reads per-fragment buffers only at non-empty
     # slots, so the step's calls leave the entries of empty slots unwritten
     skip_empty = True
+    # packed steps: the texel gather reads each kept pixel's record (taps,
+    # fractions, gradient) written by the packed backward instead of its
+    # coordinate and sample gradient; the sums are the same
+    gather_rec = True
+    inv_rec = None
 
     @contextlib.contextmanager
     def _sparse(self):
@@ -120,6 +125,24 @@ class _TwoStreams:
     def _chk2(self, rc, what, branch):
         if rc != 0:
             (self.ctx2 if self._on(branch) else self.ctx).check(rc, what)
+
+    def _gather(self, handle, inv, rec, stream, branch=None):
+        """Texel gradient of the albedo from the inverse-UV map `inv`: from the
+        pixels' records `rec`, or from their coordinates and sample gradients
+        when rec is None."""
+        S, H, W = self.B * self.K, self.H, self.W
+        if rec is not None:
+            what = "texture_grad_invrec"
+            rc = _lib.dressi_texture_grad_invrec(handle, C.byref(self.desc), S, H, W, _p(inv), _p(rec),
+                                                 _p(self.g_tex), stream)
+        else:
+            what = "texture_grad_invuv"
+            rc = _lib.dressi_texture_grad_invuv(handle, C.byref(self.desc), _p(self.uvbuf), _p(self.tri_id), S, H,
+                                                W, _p(inv), _p(self.g_samp), _p(self.g_tex), stream)
+        if branch is None:
+            self._chk(rc, what)
+        else:
+            self._chk2(rc, what, branch)
 
     def _texture_bwd(self, tex, desc, coord, S, grad_out, grad_tex, grad_coord, what):
         """Texel gradient (inverse-UV gather) on the second stream and the
@@ -274,6 +297,8 @@ class Step(_TwoStreams):
                 ps.tex, ps.td = _p(self.tex), self.desc
                 nb = int(_lib.dressi_invuv_bytes(C.byref(self.desc), B))
                 self.inv = torch.empty(nb // 4, dtype=torch.int32, device=dev)
+                # each covered pixel's gather record (taps, fractions, gradient)
+                self.inv_rec = torch.empty((B, H * W, 8), dtype=torch.float32, device=dev)
             self._pscene = ps
         # one view: the geometry adjoints as one call (dressi_geometry_bwd)
         self.packed_geo = self.packed and B == 1
@@ -437,18 +462,17 @@ class Step(_TwoStreams):
         h, s = self.ctx.handle, self._s()
         B, H, W, K = self.B, self.H, self.W, self.K
         ck = self._chk
+        rec = self.inv_rec if self.uv is not None and self.gather_rec else None
         ck(_lib.dressi_packed_backward(h, C.byref(self._pscene), _p(self.tri_id), B, H, W, _p(self.gbuf),
                                        _p(self.uvbuf), _p(self.samp), _p(self.color), _p(self.sil),
                                        _p(self.target), None, _p(self.loss), None, None, _p(self.g_gbuf),
-                                       _p(self.g_samp), _p(self.g_bary_uv), _p(self.inv), s), "packed_backward")
+                                       _p(self.g_samp), _p(self.g_bary_uv), _p(self.inv), _p(rec), s),
+           "packed_backward")
         gb_in = None
         if self.uv is not None:
             # the texel gather beside the geometry's backward ("texel" branch)
             self._fork("texel")
-            self._chk2(_lib.dressi_texture_grad_invuv(self._h2("texel"), C.byref(self.desc), _p(self.uvbuf),
-                                                      _p(self.tri_id), B * K, H, W, _p(self.inv), _p(self.g_samp),
-                                                      _p(self.g_tex), self._sa("texel")),
-                       "texture_grad_invuv", "texel")
+            self._gather(self._h2("texel"), self.inv, rec, self._sa("texel"), "texel")
             gb_in = self.g_bary_uv
         if self.packed_geo:
             ck(_lib.dressi_geometry_bwd(h, _p(self.pos), _p(self.vattr), self.V, self.Cv, _p(self.tris), self.T,
@@ -623,14 +647,14 @@ class TextureStep:
         st = self.st
         if getattr(st, "packed", False):
             h, s, ck = st.ctx.handle, st._s(), st._chk
+            rec = st.inv_rec if st.gather_rec else None
             with st._sparse():
                 ck(_lib.dressi_packed_backward(h, C.byref(st._pscene), _p(st.tri_id), st.B, st.H, st.W,
                                                _p(st.gbuf), _p(st.uvbuf), _p(st.samp), _p(st.color), _p(st.sil),
                                                _p(st.target), _p(getattr(st, "weight", None)), _p(st.loss), None,
-                                               None, None, _p(st.g_samp), None, None, s), "packed_backward")
-                ck(_lib.dressi_texture_grad_invuv(h, C.byref(st.desc), _p(st.uvbuf), _p(st.tri_id), st.B * st.K,
-                                                  st.H, st.W, _p(self.inv), _p(st.g_samp), _p(st.g_tex), s),
-                   "texture_grad_invuv")
+                                               None, None, _p(st.g_samp), None, None, _p(rec), s),
+                   "packed_backward")
+                st._gather(h, self.inv, rec, s)
             return
         self.loss_and_grad()
         self.backward()
@@ -805,6 +829,7 @@ class BatchStep(_TwoStreams):
             self._pscene = ps
             nb = int(_lib.dressi_invuv_bytes(C.byref(self.desc), 1))
             self.inv = torch.empty(nb // 4, dtype=torch.int32, device=dev)
+            self.inv_rec = torch.empty((H * W, 8), dtype=torch.float32, device=dev)
         self.hard_raster = None
         self.hybrid_weight = HYBRID_WEIGHT_DEFAULT
         self._calibrate_bins()
@@ -905,15 +930,14 @@ class BatchStep(_TwoStreams):
         and the geometry's backward as in the separate form."""
         h, st = self.ctx.handle, self._s()
         H, W, T = self.H, self.W, self.T
+        rec = self.inv_rec if self.gather_rec else None
         self._chk(_lib.dressi_packed_backward(h, C.byref(self._pscene), _p(self.tri_id), 1, H, W, _p(self.gbuf),
                                               _p(self.uvbuf), _p(self.samp), _p(self.color), _p(self.sil),
                                               _p(self.target), _p(self.weight), _p(self.loss), None, None,
                                               _p(self.g_gbuf), _p(self.g_samp), _p(self.g_bary_uv), _p(self.inv),
-                                              st), "packed_backward")
+                                              _p(rec), st), "packed_backward")
         self._fork("texel")
-        self._chk2(_lib.dressi_texture_grad_invuv(self._h2("texel"), C.byref(self.desc), _p(self.uvbuf),
-                                                  _p(self.tri_id), 1, H, W, _p(self.inv), _p(self.g_samp),
-                                                  _p(self.g_tex), self._sa("texel")), "texture_grad_invuv", "texel")
+        self._gather(self._h2("texel"), self.inv, rec, self._sa("texel"), "texel")
         ck = self._chk
         V, T = self.V, self.T
         ck(_lib.dressi_geometry_bwd(h, _p(self.pos), _p(self.vattr), V, 6, _p(self.tris), T, _p(self.pos_clip),

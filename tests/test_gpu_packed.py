@@ -200,3 +200,61 @@ def test_packed_uneven_batch_matches_separate_stages(Bd, skip_empty):
     assert abs(La - Lb) <= 1e-6 * Lb, (La, Lb)
     assert np.array_equal(pa, pb), "position gradient differs"
     assert np.array_equal(ta, tb), "texture gradient differs"
+
+
+@pytest.mark.parametrize("which", ["ragged", "uneven"])
+def test_gather_records_match_coordinate_gather(Bd, which):
+    """The texel gather from the packed backward's per-pixel records
+    (dressi_texture_grad_invrec) gives bitwise the gather from coordinates and
+    sample gradients (dressi_texture_grad_invuv) on the same map: two views of
+    a ragged image, and an uneven batch (texture array, one layer each)."""
+    from paper_2204_01386_amd.pipeline import BatchStep, Step, make_batch_target, make_target
+    out = {}
+    for rec in (True, False):
+        if which == "ragged":
+            s = _ragged_two_views(7)
+            st = Step(s, target=make_target(s))
+        else:
+            sl = scenes.config4(seed=4, n=5, t_min=200, t_max=2e4, sizes=(128, 256), tex_size=128)
+            st = BatchStep(sl, target=make_batch_target(sl))
+        assert st.packed and st.inv_rec is not None
+        st.gather_rec = rec
+        st.run()
+        torch.cuda.synchronize()
+        out[rec] = (host(st.g_tex).copy(), host(st.g_pos).copy())
+    assert np.abs(out[True][0]).max() > 0
+    assert np.array_equal(out[True][0], out[False][0]), "texture gradient differs"
+    assert np.array_equal(out[True][1], out[False][1]), "position gradient differs"
+
+
+def test_gather_record_entry_point_checks(Bd):
+    """dressi_texture_grad_invrec refuses a cube map, a texture that is not
+    RGBA and unaligned records; dressi_packed_backward refuses unaligned
+    records and records for the untextured pass."""
+    from paper_2204_01386_amd.pipeline import Step, _p
+    s = scenes.config2(H=32, subdiv=2, tex_size=16)
+    st = Step(s)
+    lib, h = Bd._lib, st.ctx.handle
+    stream = Bd._stream()
+
+    def gather(desc, rec_ptr):
+        return lib.dressi_texture_grad_invrec(h, C.byref(desc), 1, st.H, st.W, _p(st.inv), rec_ptr,
+                                              _p(st.g_tex), stream)
+
+    assert gather(st.desc, _p(st.inv_rec)) == 0
+    d = Bd.TexDesc.from_buffer_copy(st.desc); d.kind = Bd.TEX_CUBE; d.Wt = d.Ht
+    assert gather(d, _p(st.inv_rec)) == Bd.EINVAL
+    d = Bd.TexDesc.from_buffer_copy(st.desc); d.Ct = 3
+    assert gather(d, _p(st.inv_rec)) == Bd.EINVAL
+    assert gather(st.desc, C.c_void_p(st.inv_rec.data_ptr() + 4)) == Bd.EINVAL
+
+    def bwd(ps, rec_ptr):
+        return lib.dressi_packed_backward(h, C.byref(ps), _p(st.tri_id), 1, st.H, st.W, _p(st.gbuf), _p(st.uvbuf),
+                                          _p(st.samp), _p(st.color), _p(st.sil), _p(st.target), None, _p(st.loss),
+                                          None, None, _p(st.g_gbuf), _p(st.g_samp), _p(st.g_bary_uv), _p(st.inv),
+                                          rec_ptr, stream)
+
+    assert bwd(st._pscene, C.c_void_p(st.inv_rec.data_ptr() + 4)) == Bd.EINVAL
+    ps = Bd.PackedScene.from_buffer_copy(st._pscene); ps.mode = Bd.SHADE_LAMBERT; ps.Cv = 9
+    assert bwd(ps, _p(st.inv_rec)) == Bd.EINVAL
+    torch.cuda.synchronize()
