@@ -441,6 +441,14 @@ int dressi_vertex_attrs(dressi_ctx *ctx, const float *pos, const int32_t *tris, 
 int dressi_vertex_attrs_bwd(dressi_ctx *ctx, const float *pos, const int32_t *tris, int V, int T,
                             int C, const int32_t *adj, const float *grad_out,
                             const float *grad_pos_in, float *grad_pos, void *stream);
+/* dressi_vertex_attrs (vattr [V,C]) and the vertex transform in one launch,
+ * the same values: pos_clip [B,V,4] as dressi_transform with B views of mvp
+ * [B,4,4], or, with vert_view (B = 1), [V,4] as dressi_transform_batched.
+ * adj as for dressi_vertex_attrs.  DRESSI_EINVAL for B < 1, or B != 1 with
+ * vert_view. */
+int dressi_vertex_stage(dressi_ctx *ctx, const float *pos, const int32_t *tris, int V, int T,
+                        const float *extra, const int32_t *adj, const float *mvp, const int32_t *vert_view,
+                        int B, float *vattr, float *pos_clip, void *stream);
 
 #define DRESSI_SHADE_LAMBERT 0   /* c = a (0.1 + 0.9 max(0, n.l))                         */
 #define DRESSI_SHADE_PHONG 1     /* c = a_rgb (0.1 + 0.8 max(0,n.l)) + 0.2 a_a max(0,r.v)^32 */

@@ -113,6 +113,7 @@ _SIG = {
     "dressi_transform_bwd": [_vp, _vp, _i, _i, _vp, _vp, _vp],
     "dressi_vertex_attrs": [_vp, _vp, _vp, _i, _i, _vp, _vp, _vp, _vp],
     "dressi_vertex_attrs_bwd": [_vp, _vp, _vp, _i, _i, _i, _vp, _vp, _vp, _vp, _vp],
+    "dressi_vertex_stage": [_vp, _vp, _vp, _i, _i, _vp, _vp, _vp, _vp, _i, _vp, _vp, _vp],
     "dressi_adjacency": [_vp, _vp, _i, _i, _vp, _vp],
     "dressi_fragment_index": [_vp, _vp, _i, _i, _i, _i, _i, _vp, _vp],
     "dressi_shade": [_vp, _i, _vp, _vp, _vp, _i, _i64, _vp, _vp, _vp],

@@ -185,6 +185,42 @@ __global__ void k_vertex_attrs(const float *__restrict__ pos, const int32_t *__r
     }
 }
 
+// The vertex attributes of k_vertex_attrs and the clip positions of
+// k_transform in one launch, with the arithmetic of both: the vertex's lanes
+// sum its face normals as above; lane j transforms it for the views j, j +
+// VA_LANES, ... (with vert_view, lane 0 for its own view) and lane 0 writes
+// its attribute row.
+__global__ void k_vertex_stage(const float *__restrict__ pos, const int32_t *__restrict__ tris,
+                               const float *__restrict__ extra, Adjacency adj, int V, int C,
+                               float *__restrict__ out, const float *__restrict__ mvp,
+                               const int32_t *__restrict__ vert_view, int B, float4 *__restrict__ pos_clip) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int v = (int)(gid / VA_LANES), slot = (int)(gid % VA_LANES);
+    const bool live = v < V;
+    const dbl3 a = vertex_acc(pos, tris, adj, v, V, live, slot);
+    if (!live) return;
+    const float x = pos[3 * (int64_t)v], y = pos[3 * (int64_t)v + 1], z = pos[3 * (int64_t)v + 2];
+    const int nb = vert_view ? 1 : B;
+    for (int b = slot; b < nb; b += VA_LANES) {
+        const float *M = mvp + 16 * (int64_t)(vert_view ? vert_view[v] : b);
+        float4 o;
+        o.x = M[0] * x + M[1] * y + M[2] * z + M[3];
+        o.y = M[4] * x + M[5] * y + M[6] * z + M[7];
+        o.z = M[8] * x + M[9] * y + M[10] * z + M[11];
+        o.w = M[12] * x + M[13] * y + M[14] * z + M[15];
+        pos_clip[(int64_t)b * V + v] = o;
+    }
+    if (slot != 0) return;
+    const double l = sqrt(a.x * a.x + a.y * a.y + a.z * a.z);
+    const double il = l > 0.0 ? 1.0 / l : 0.0;
+    float *o = out + (int64_t)v * C;
+    o[0] = (float)(a.x * il); o[1] = (float)(a.y * il); o[2] = (float)(a.z * il);
+    o[3] = x; o[4] = y; o[5] = z;
+    if (C == 9) {
+        o[6] = extra[3 * (int64_t)v]; o[7] = extra[3 * (int64_t)v + 1]; o[8] = extra[3 * (int64_t)v + 2];
+    }
+}
+
 // gradient w.r.t. the un-normalised vertex normal sum
 __global__ void k_vertex_attrs_bwd1(const float *__restrict__ pos, const int32_t *__restrict__ tris,
                                     Adjacency adj, int V, int C, const float *__restrict__ g,
@@ -401,6 +437,33 @@ extern "C" int dressi_vertex_attrs(dressi_ctx *ctx, const float *pos, const int3
     const int nb = (int)(((int64_t)V * VA_LANES + 255) / 256);
     DR_LAUNCH("k_vertex_attrs", (k_vertex_attrs), nb, 256, 0, st, pos, tris, extra, A, V, C, out);
     return dressi_launch_check(ctx, "vertex_attrs");
+}
+
+extern "C" int dressi_vertex_stage(dressi_ctx *ctx, const float *pos, const int32_t *tris, int V, int T,
+                                   const float *extra, const int32_t *adj, const float *mvp,
+                                   const int32_t *vert_view, int B, float *vattr, float *pos_clip, void *stream) {
+    if (!ctx) return DRESSI_EINVAL;
+    if (V < 0 || T < 0 || B < 1 || (vert_view && B != 1))
+        return dressi_fail(ctx, DRESSI_EINVAL, "vertex_stage: bad dimensions (B >= 1; 1 with vert_view)");
+    if (V == 0) return DRESSI_OK;
+    if (!pos || !vattr || !mvp || !pos_clip || (T > 0 && !tris))
+        return dressi_fail(ctx, DRESSI_EINVAL, "vertex_stage: null pointer");
+    hipStream_t st = (hipStream_t)stream;
+    const int32_t *ab = adj;
+    if (!ab) {
+        Carver c;
+        size_t o_adj = c.take(adjacency_buf_bytes(V, T));
+        size_t o_tmp = c.take(dressi_adjacency_tmp_bytes(V, T));
+        int rc = dressi_scratch(ctx, c.off, st);
+        if (rc) return rc;
+        int32_t *buf = at<int32_t>(ctx->scratch, o_adj);
+        dressi_build_adjacency_into(tris, T, V, buf, at<void>(ctx->scratch, o_tmp), st);
+        ab = buf;
+    }
+    const int nb = (int)(((int64_t)V * VA_LANES + 255) / 256);
+    DR_LAUNCH("k_vertex_stage", (k_vertex_stage), nb, 256, 0, st, pos, tris, extra, adjacency_view(ab, V), V,
+              extra ? 9 : 6, vattr, mvp, vert_view, B, reinterpret_cast<float4 *>(pos_clip));
+    return dressi_launch_check(ctx, "vertex_stage");
 }
 
 extern "C" int dressi_vertex_attrs_bwd(dressi_ctx *ctx, const float *pos, const int32_t *tris, int V,

@@ -306,12 +306,19 @@ class Step(_TwoStreams):
         self.hybrid_weight = HYBRID_WEIGHT_DEFAULT
         self._calibrate_bins()
 
-    def _raster(self):
+    def _raster(self, attrs=False):
+        """Transform and rasterization; with `attrs`, the vertex attributes
+        in the transform's launch (dressi_vertex_stage)."""
         h, st = self.ctx.handle, self._s()
         self.ctx.tune(Bd.TUNE_HARD_RASTER, self.hard_raster or 0)
         self.ctx.tune(Bd.TUNE_HYBRID_WEIGHT, self.hybrid_weight)
-        self._chk(_lib.dressi_transform(h, _p(self.pos), _p(self.mvp), self.B, self.V, _p(self.pos_clip), st),
-                  "transform")
+        if attrs:
+            self._chk(_lib.dressi_vertex_stage(h, _p(self.pos), _p(self.tris), self.V, self.T, _p(self.extra),
+                                               _p(self.adj), _p(self.mvp), None, self.B, _p(self.vattr),
+                                               _p(self.pos_clip), st), "vertex_stage")
+        else:
+            self._chk(_lib.dressi_transform(h, _p(self.pos), _p(self.mvp), self.B, self.V, _p(self.pos_clip),
+                                            st), "transform")
         if self.band:
             self._chk(_lib.dressi_rasterize_banded(h, _p(self.pos_clip), _p(self.tris), self.B, self.V, self.T,
                                                    self.H, self.W, self.K, self.r, 0, self.delta, self.blend,
@@ -369,12 +376,17 @@ class Step(_TwoStreams):
         h, s = self.ctx.handle, self._s()
         B, V, T, H, W, K = self.B, self.V, self.T, self.H, self.W, self.K
         ck = self._chk
-        # vertex attributes beside transform + rasterization
-        self._fork("attrs")
-        self._chk2(_lib.dressi_vertex_attrs(self._h2("attrs"), _p(self.pos), _p(self.tris), V, T, _p(self.extra),
-                                            _p(self.adj), _p(self.vattr), self._sa("attrs")), "vertex_attrs", "attrs")
-        self._raster()
-        self._join()
+        # vertex attributes beside transform + rasterization, or in the
+        # transform's launch
+        if self._on("attrs"):
+            self._fork("attrs")
+            self._chk2(_lib.dressi_vertex_attrs(self._h2("attrs"), _p(self.pos), _p(self.tris), V, T,
+                                                _p(self.extra), _p(self.adj), _p(self.vattr), self._sa("attrs")),
+                       "vertex_attrs", "attrs")
+            self._raster()
+            self._join()
+        else:
+            self._raster(attrs=True)
         # the backward's fragment index beside the rest of the forward
         self._fork("index")
         self._chk2(_lib.dressi_fragment_index(self._h2("index"), _p(self.tri_id), B, K, H, W, T, _p(self.frag_index),
@@ -841,12 +853,17 @@ class BatchStep(_TwoStreams):
         if rc != 0:
             self.ctx.check(rc, what)
 
-    def _raster(self):
+    def _raster(self, attrs=False):
         h, st = self.ctx.handle, self._s()
         self.ctx.tune(Bd.TUNE_HARD_RASTER, self.hard_raster or 0)
         self.ctx.tune(Bd.TUNE_HYBRID_WEIGHT, self.hybrid_weight)
-        self._chk(_lib.dressi_transform_batched(h, _p(self.pos), _p(self.vert_view), _p(self.mvp), self.V,
-                                                _p(self.pos_clip), st), "transform_batched")
+        if attrs:
+            self._chk(_lib.dressi_vertex_stage(h, _p(self.pos), _p(self.tris), self.V, self.T, None, _p(self.adj),
+                                               _p(self.mvp), _p(self.vert_view), 1, _p(self.vattr),
+                                               _p(self.pos_clip), st), "vertex_stage")
+        else:
+            self._chk(_lib.dressi_transform_batched(h, _p(self.pos), _p(self.vert_view), _p(self.mvp), self.V,
+                                                    _p(self.pos_clip), st), "transform_batched")
         self._chk(_lib.dressi_rasterize_batched(h, _p(self.pos_clip), _p(self.tris), _p(self.tri_view),
                                                 _p(self.views), self.n, self.V, self.T, self.H, self.W, 1, 0,
                                                 _p(self.tri_id), _p(self.bary), st), "rasterize_batched")
@@ -870,11 +887,15 @@ class BatchStep(_TwoStreams):
     def _forward(self):
         h, st = self.ctx.handle, self._s()
         H, W, V, T, ck = self.H, self.W, self.V, self.T, self._chk
-        self._fork("attrs")
-        self._chk2(_lib.dressi_vertex_attrs(self._h2("attrs"), _p(self.pos), _p(self.tris), V, T, None, _p(self.adj),
-                                            _p(self.vattr), self._sa("attrs")), "vertex_attrs", "attrs")
-        self._raster()
-        self._join()
+        if self._on("attrs"):
+            self._fork("attrs")
+            self._chk2(_lib.dressi_vertex_attrs(self._h2("attrs"), _p(self.pos), _p(self.tris), V, T, None,
+                                                _p(self.adj), _p(self.vattr), self._sa("attrs")), "vertex_attrs",
+                       "attrs")
+            self._raster()
+            self._join()
+        else:
+            self._raster(attrs=True)
         self._fork("index")
         self._chk2(_lib.dressi_fragment_index(self._h2("index"), _p(self.tri_id), 1, 1, H, W, T, _p(self.frag_index),
                                               self._sa("index")), "fragment_index", "index")

@@ -585,3 +585,21 @@ def test_fragment_index_scan_across_many_blocks(B, n_keys):
     assert np.abs(ga).max() > 0
     assert np.array_equal(ga_p[:V], ga) and not ga_p[V:].any()
     assert np.array_equal(host(gb_p), host(gb))
+
+
+@pytest.mark.parametrize("V", [16384, 16385, 81921, 2048 * 1024 + 1])
+def test_adjacency_offsets_are_the_exclusive_scan(B, V):
+    """The vertex -> corner offsets are the exclusive scan of the vertices'
+    corner counts: on both sides of the one-workgroup scan's limit (16,384),
+    mid-size and past 2,048 blocks of the two-pass scan, against numpy's
+    cumulative sum of the counts, with every corner listed under its vertex."""
+    rng = np.random.default_rng(V)
+    T = V
+    tris = rng.integers(0, V, (T, 3)).astype(np.int32)
+    a = host(B.dressi_adjacency(dev(tris), V))
+    counts = np.bincount(tris.ravel(), minlength=V)
+    ref = np.concatenate([[0], np.cumsum(counts)]).astype(np.int32)
+    assert np.array_equal(a[:V + 1], ref)
+    corners = a[V + 1:]
+    for v in rng.integers(0, V, 8):
+        assert np.array_equal(corners[ref[v]:ref[v + 1]], np.nonzero(tris.ravel() == v)[0])

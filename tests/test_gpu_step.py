@@ -49,6 +49,58 @@ def test_vertex_attrs(B, extra):
     assert_grad_close(host(gp), ref_g, what="vertex_attrs_bwd")
 
 
+@pytest.mark.parametrize("views,extra,own_adj", [(1, False, True), (3, True, True), (9, False, False),
+                                                 ("batched", False, True)])
+def test_vertex_stage_is_attrs_and_transform(B, views, extra, own_adj):
+    """dressi_vertex_stage gives bitwise the vertex attributes of
+    dressi_vertex_attrs and the clip positions of dressi_transform (1, 3 and
+    9 views: more views than lanes per vertex) or dressi_transform_batched
+    (a matrix per vertex), with the adjacency given or built inside; B < 1,
+    or B != 1 with vert_view, is refused."""
+    import ctypes as C
+    lib = B._lib
+    p, tris = scenes.noisy_sphere(3, 2)
+    V, T = p.shape[0], tris.shape[0]
+    rng = np.random.default_rng(5)
+    ex = rng.random(p.shape).astype(np.float32) if extra else None
+    nb = 4 if views == "batched" else views
+    s = scenes.config3(n_views=nb, subdiv=1, H=16, tex_size=8, env_size=4)
+    mvp = s.mvp
+    vv = rng.integers(0, nb, V).astype(np.int32) if views == "batched" else None
+    ref_attr = host(B.dressi_vertex_attrs(dev(p), dev(tris), dev(ex) if extra else None))
+    if vv is None:
+        ref_clip = host(B.dressi_transform(dev(p), dev(mvp)))
+    else:
+        ref_clip = oracle.transform_f32(p, mvp)[vv, np.arange(V)]
+    adj = B.dressi_adjacency(dev(tris), V) if own_adj else None
+    attr = torch.empty((V, 9 if extra else 6), device="cuda")
+    clip = torch.empty((1 if vv is not None else nb, V, 4), device="cuda")
+    ctx = B.context()
+    pp, tt, mm = dev(p), dev(tris), dev(mvp)
+    ee = dev(ex) if extra else None
+    vvd = dev(vv) if vv is not None else None
+
+    def call(Bn, vptr):
+        return lib.dressi_vertex_stage(ctx.handle, C.c_void_p(pp.data_ptr()), C.c_void_p(tt.data_ptr()), V, T,
+                                       C.c_void_p(ee.data_ptr()) if ee is not None else None,
+                                       C.c_void_p(adj.data_ptr()) if adj is not None else None,
+                                       C.c_void_p(mm.data_ptr()), vptr, Bn, C.c_void_p(attr.data_ptr()),
+                                       C.c_void_p(clip.data_ptr()), B._stream())
+
+    vptr = C.c_void_p(vvd.data_ptr()) if vvd is not None else None
+    assert call(1 if vv is not None else nb, vptr) == 0
+    torch.cuda.synchronize()
+    assert np.array_equal(host(attr), ref_attr), "vertex attributes differ"
+    got = host(clip)
+    if vv is not None:
+        assert np.array_equal(got[0], ref_clip), "clip positions differ (per-vertex matrix)"
+        assert call(2, vptr) == B.EINVAL
+    else:
+        assert np.array_equal(got, ref_clip), "clip positions differ"
+    assert call(0, None) == B.EINVAL
+    torch.cuda.synchronize()
+
+
 def _frag_inputs(rng, Bn, N):
     n = rng.standard_normal((Bn, N, 3)).astype(np.float32)
     t = rng.standard_normal((Bn, N, 3)).astype(np.float32)
