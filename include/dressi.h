@@ -559,14 +559,18 @@ int dressi_packed_forward(dressi_ctx *ctx, const dressi_packed_scene *scene, con
  * 16-byte aligned): the record of every covered pixel that a map registers
  * (here in inv, or earlier by dressi_invuv_build on the same coordinates)
  * for dressi_texture_grad_invrec, the faster gather; other entries are
- * left as they were.  Inputs are the forward's outputs.  Phong: grad_gbuf and
- * grad_bary_uv may be NULL (only the albedo sample's gradient, as a
- * texture-only step needs). */
+ * left as they were.  grad_tex (nullable; needs inv and inv_rec, 16-byte
+ * aligned, Ht, Wt >= 3 for repeat wrap): the texture gradient as
+ * dressi_texture_grad_invrec gives it from this call's map and records,
+ * gathered in this call (the loss's last sum rides in the gather's launch).
+ * Inputs are the forward's outputs.  Phong: grad_gbuf and grad_bary_uv may
+ * be NULL (only the albedo sample's gradient, as a texture-only step needs). */
 int dressi_packed_backward(dressi_ctx *ctx, const dressi_packed_scene *scene, const int32_t *tri_id, int B,
                            int H, int W, const float *gbuf, const float *uvbuf, const float *samp,
                            const float *color, const float *sil, const float *target, const float *weight,
                            float *loss, float *grad_color, float *grad_sil, float *grad_gbuf,
-                           float *grad_samp, float *grad_bary_uv, int32_t *inv, void *inv_rec, void *stream);
+                           float *grad_samp, float *grad_bary_uv, int32_t *inv, void *inv_rec, float *grad_tex,
+                           void *stream);
 
 /* Geometry adjoints of one image (B = 1, K = 1, hard: after the packed
  * pass), in three launches: the same values as dressi_interpolate_bwd of

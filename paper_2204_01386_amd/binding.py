@@ -123,7 +123,7 @@ _SIG = {
                             _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
     "dressi_packed_forward": [_vp, _vp, _vp, _vp, _i, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
     "dressi_packed_backward": [_vp, _vp, _vp, _i, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
-                               _vp, _vp, _vp, _vp, _vp, _vp],
+                               _vp, _vp, _vp, _vp, _vp, _vp, _vp],
     "dressi_texture_grad_invrec": [_vp, _vp, _i, _i, _i, _vp, _vp, _vp, _vp],
     "dressi_transform_batched": [_vp, _vp, _vp, _vp, _i, _vp, _vp],
     "dressi_tune": [_vp, _i, _i64],

@@ -97,6 +97,42 @@ static inline size_t dressi_invuv_part_bytes(int64_t cells, int Ct, int S) {
     return ns > 1 ? sizeof(float) * (size_t)cells * Ct * ns : 0;
 }
 
+// The last step of a loss: its per-block partials added by one 256-lane
+// workgroup (lane i takes the partials i, i + 256, ... in order, eight loads
+// in flight, then a fixed tree), loss[0] = scale * sum.  `red` is 256 floats
+// of LDS.  Used by k_loss_sum and, riding in the texel gather's launch, by
+// the packed backward.
+struct LossJob {
+    const float *partial;
+    int nb;
+    float scale;
+    float *loss;   // NULL: no job
+};
+__device__ __forceinline__ void loss_sum_block(const LossJob &j, float *red) {
+    float a = 0.0f;
+    for (int i = threadIdx.x; i < j.nb; i += 8 * 256) {
+        float v[8];
+#pragma unroll
+        for (int q = 0; q < 8; q++) v[q] = i + q * 256 < j.nb ? j.partial[i + q * 256] : 0.0f;
+#pragma unroll
+        for (int q = 0; q < 8; q++)
+            if (i + q * 256 < j.nb) a += v[q];
+    }
+    red[threadIdx.x] = a;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) j.loss[0] = red[0] * j.scale;
+}
+
+// Texel gather from per-pixel records (texture.hip), with an optional loss
+// job in an extra workgroup of its launch; part: scratch of
+// dressi_invuv_part_bytes(cells, 4, S).
+void dr_gather_invrec(const dressi_tex_desc &td, int S, int64_t npix, const int32_t *inv, const int4 *rec,
+                      float *part, float *grad_tex, hipStream_t st, int rows, LossJob lj);
+
 // Bump allocator over the arena: carve(n) returns 256-byte aligned offsets.
 struct Carver {
     size_t off = 0;

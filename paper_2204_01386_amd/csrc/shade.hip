@@ -868,24 +868,9 @@ __global__ void __launch_bounds__(LOSS_BS)
 
 __global__ void __launch_bounds__(LOSS_BS)
     k_loss_sum(const float *__restrict__ partial, int nb, float scale, float *__restrict__ loss) {
+    static_assert(LOSS_BS == 256, "loss_sum_block is one 256-lane workgroup");
     __shared__ float red[LOSS_BS];
-    float a = 0.0f;
-    // the partials i, i + LOSS_BS, ... in order; eight loads in flight
-    for (int i = threadIdx.x; i < nb; i += 8 * LOSS_BS) {
-        float v[8];
-#pragma unroll
-        for (int j = 0; j < 8; j++) v[j] = i + j * LOSS_BS < nb ? partial[i + j * LOSS_BS] : 0.0f;
-#pragma unroll
-        for (int j = 0; j < 8; j++)
-            if (i + j * LOSS_BS < nb) a += v[j];
-    }
-    red[threadIdx.x] = a;
-    __syncthreads();
-    for (int s = LOSS_BS / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) loss[0] = red[0] * scale;
+    loss_sum_block(LossJob{partial, nb, scale, loss}, red);
 }
 
 extern "C" int dressi_loss_l2(dressi_ctx *ctx, const float *color, const float *sil, const float *target,
@@ -1206,7 +1191,7 @@ extern "C" int dressi_packed_backward(dressi_ctx *ctx, const dressi_packed_scene
                                       const float *samp, const float *color, const float *sil,
                                       const float *target, const float *weight, float *loss, float *grad_color,
                                       float *grad_sil, float *grad_gbuf, float *grad_samp, float *grad_bary_uv,
-                                      int32_t *inv, void *inv_rec, void *stream) {
+                                      int32_t *inv, void *inv_rec, float *grad_tex, void *stream) {
     int rc = check_packed(ctx, sc, B, H, W, "packed_backward");
     if (rc) return rc;
     const int64_t npix = (int64_t)H * W, n = (int64_t)B * npix;
@@ -1215,6 +1200,11 @@ extern "C" int dressi_packed_backward(dressi_ctx *ctx, const dressi_packed_scene
     if (inv && !tex) return dressi_fail(ctx, DRESSI_EINVAL, "packed_backward: inv is for the textured (Phong) pass");
     if (inv_rec && (!tex || !al16(inv_rec)))
         return dressi_fail(ctx, DRESSI_EINVAL, "packed_backward: inv_rec is for the textured pass, 16-byte aligned");
+    if (grad_tex && (!inv || !inv_rec || !al16(grad_tex)))
+        return dressi_fail(ctx, DRESSI_EINVAL, "packed_backward: grad_tex needs inv, inv_rec and 16-byte alignment");
+    if (grad_tex && ((sc->td.wrap_u == DRESSI_WRAP_REPEAT && sc->td.Wt < 3) ||
+                     (sc->td.wrap_v == DRESSI_WRAP_REPEAT && sc->td.Ht < 3)))
+        return dressi_fail(ctx, DRESSI_EINVAL, "packed_backward: repeat wrap needs at least 3 texels");
     if (n > 0 && (!tri_id || !gbuf || !color || !sil || !target || (!tex && !grad_gbuf) ||
                   (tex && (!uvbuf || !samp || !grad_samp))))
         return dressi_fail(ctx, DRESSI_EINVAL, "packed_backward: null input or output");
@@ -1224,6 +1214,8 @@ extern "C" int dressi_packed_backward(dressi_ctx *ctx, const dressi_packed_scene
     const int64_t nb = n > 0 ? std::min<int64_t>((n + 255) / 256, PACKED_MAX_BLOCKS) : 1;
     Carver c;
     const size_t o_p = c.take(sizeof(float) * (size_t)nb);
+    const int64_t cells = tex ? (int64_t)tex_faces(sc->td) * sc->td.Ht * sc->td.Wt : 0;
+    const size_t o_g = grad_tex ? c.take(dressi_invuv_part_bytes(cells, 4, B)) : 0;
     if ((rc = dressi_scratch(ctx, c.off, st))) return rc;
     float *partial = at<float>(ctx->scratch, o_p);
     const float w = 1.0f / (4.0f * (float)(n > 0 ? n : 1));
@@ -1240,6 +1232,13 @@ extern "C" int dressi_packed_backward(dressi_ctx *ctx, const dressi_packed_scene
                   gbuf, uvbuf, samp, color, sil, t4, weight, w, grad_color, grad_sil, grad_gbuf, grad_samp, gb, inv,
                   nullptr, partial, ctx->skip_empty);
     }
-    DR_LAUNCH("k_loss_sum", (k_loss_sum), 1, LOSS_BS, 0, st, partial, (int)nb, weight ? 1.0f : w, loss);
+    const LossJob lj{partial, (int)nb, weight ? 1.0f : w, loss};
+    if (grad_tex) {
+        // the texel gather, with the loss's last sum in an extra workgroup of its launch
+        dr_gather_invrec(sc->td, B, npix, inv, static_cast<const int4 *>(inv_rec), at<float>(ctx->scratch, o_g),
+                         grad_tex, st, ctx->iv_rows, lj);
+    } else {
+        DR_LAUNCH("k_loss_sum", (k_loss_sum), 1, LOSS_BS, 0, st, lj.partial, lj.nb, lj.scale, lj.loss);
+    }
     return dressi_launch_check(ctx, "packed_backward");
 }

@@ -474,17 +474,20 @@ class Step(_TwoStreams):
         h, s = self.ctx.handle, self._s()
         B, H, W, K = self.B, self.H, self.W, self.K
         ck = self._chk
+        # with records, the texel gather runs inside the packed backward
+        # (with the loss's last sum in its launch)
         rec = self.inv_rec if self.uv is not None and self.gather_rec else None
         ck(_lib.dressi_packed_backward(h, C.byref(self._pscene), _p(self.tri_id), B, H, W, _p(self.gbuf),
                                        _p(self.uvbuf), _p(self.samp), _p(self.color), _p(self.sil),
                                        _p(self.target), None, _p(self.loss), None, None, _p(self.g_gbuf),
-                                       _p(self.g_samp), _p(self.g_bary_uv), _p(self.inv), _p(rec), s),
-           "packed_backward")
+                                       _p(self.g_samp), _p(self.g_bary_uv), _p(self.inv), _p(rec),
+                                       _p(self.g_tex if rec is not None else None), s), "packed_backward")
         gb_in = None
         if self.uv is not None:
-            # the texel gather beside the geometry's backward ("texel" branch)
-            self._fork("texel")
-            self._gather(self._h2("texel"), self.inv, rec, self._sa("texel"), "texel")
+            if rec is None:
+                # the texel gather beside the geometry's backward ("texel" branch)
+                self._fork("texel")
+                self._gather(self._h2("texel"), self.inv, None, self._sa("texel"), "texel")
             gb_in = self.g_bary_uv
         if self.packed_geo:
             ck(_lib.dressi_geometry_bwd(h, _p(self.pos), _p(self.vattr), self.V, self.Cv, _p(self.tris), self.T,
@@ -664,7 +667,7 @@ class TextureStep:
                 ck(_lib.dressi_packed_backward(h, C.byref(st._pscene), _p(st.tri_id), st.B, st.H, st.W,
                                                _p(st.gbuf), _p(st.uvbuf), _p(st.samp), _p(st.color), _p(st.sil),
                                                _p(st.target), _p(getattr(st, "weight", None)), _p(st.loss), None,
-                                               None, None, _p(st.g_samp), None, None, _p(rec), s),
+                                               None, None, _p(st.g_samp), None, None, _p(rec), None, s),
                    "packed_backward")
                 st._gather(h, self.inv, rec, s)
             return
@@ -951,14 +954,17 @@ class BatchStep(_TwoStreams):
         and the geometry's backward as in the separate form."""
         h, st = self.ctx.handle, self._s()
         H, W, T = self.H, self.W, self.T
+        # with records, the texel gather runs inside the packed backward
         rec = self.inv_rec if self.gather_rec else None
         self._chk(_lib.dressi_packed_backward(h, C.byref(self._pscene), _p(self.tri_id), 1, H, W, _p(self.gbuf),
                                               _p(self.uvbuf), _p(self.samp), _p(self.color), _p(self.sil),
                                               _p(self.target), _p(self.weight), _p(self.loss), None, None,
                                               _p(self.g_gbuf), _p(self.g_samp), _p(self.g_bary_uv), _p(self.inv),
-                                              _p(rec), st), "packed_backward")
-        self._fork("texel")
-        self._gather(self._h2("texel"), self.inv, rec, self._sa("texel"), "texel")
+                                              _p(rec), _p(self.g_tex if rec is not None else None), st),
+                  "packed_backward")
+        if rec is None:
+            self._fork("texel")
+            self._gather(self._h2("texel"), self.inv, None, self._sa("texel"), "texel")
         ck = self._chk
         V, T = self.V, self.T
         ck(_lib.dressi_geometry_bwd(h, _p(self.pos), _p(self.vattr), V, 6, _p(self.tris), T, _p(self.pos_clip),

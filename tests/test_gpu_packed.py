@@ -230,7 +230,8 @@ def test_gather_records_match_coordinate_gather(Bd, which):
 def test_gather_record_entry_point_checks(Bd):
     """dressi_texture_grad_invrec refuses a cube map, a texture that is not
     RGBA and unaligned records; dressi_packed_backward refuses unaligned
-    records and records for the untextured pass."""
+    records, records for the untextured pass, and a texture gradient without
+    records or unaligned."""
     from paper_2204_01386_amd.pipeline import Step, _p
     s = scenes.config2(H=32, subdiv=2, tex_size=16)
     st = Step(s)
@@ -248,13 +249,16 @@ def test_gather_record_entry_point_checks(Bd):
     assert gather(d, _p(st.inv_rec)) == Bd.EINVAL
     assert gather(st.desc, C.c_void_p(st.inv_rec.data_ptr() + 4)) == Bd.EINVAL
 
-    def bwd(ps, rec_ptr):
+    def bwd(ps, rec_ptr, gt_ptr=None):
         return lib.dressi_packed_backward(h, C.byref(ps), _p(st.tri_id), 1, st.H, st.W, _p(st.gbuf), _p(st.uvbuf),
                                           _p(st.samp), _p(st.color), _p(st.sil), _p(st.target), None, _p(st.loss),
                                           None, None, _p(st.g_gbuf), _p(st.g_samp), _p(st.g_bary_uv), _p(st.inv),
-                                          rec_ptr, stream)
+                                          rec_ptr, gt_ptr, stream)
 
     assert bwd(st._pscene, C.c_void_p(st.inv_rec.data_ptr() + 4)) == Bd.EINVAL
     ps = Bd.PackedScene.from_buffer_copy(st._pscene); ps.mode = Bd.SHADE_LAMBERT; ps.Cv = 9
     assert bwd(ps, _p(st.inv_rec)) == Bd.EINVAL
+    # the gather inside the backward needs the records and an aligned gradient
+    assert bwd(st._pscene, None, _p(st.g_tex)) == Bd.EINVAL
+    assert bwd(st._pscene, _p(st.inv_rec), C.c_void_p(st.g_tex.data_ptr() + 4)) == Bd.EINVAL
     torch.cuda.synchronize()
