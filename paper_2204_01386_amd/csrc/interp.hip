@@ -207,7 +207,7 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX)
     for (int r = p; r < nr; r += DRESSI_TILE_PIX) {
         int j0 = fl.rec_start[base + r];
         int j1 = (r + 1 < nr) ? fl.rec_start[base + r + 1] : nf;
-        ib_record(vals, S, C, fl, base, j0, j1, partial + (base + r) * 3 * C);
+        ib_record(vals, S, C, fl.frag + base, j0, j1, partial + (base + r) * 3 * C);
     }
 }
 

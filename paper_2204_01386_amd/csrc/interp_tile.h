@@ -89,7 +89,8 @@ __device__ __forceinline__ bool ib_fragment(const float *__restrict__ ab, int Va
 
 // One record of the per-tile sums: the fragments [j0, j1) of the tile's
 // sorted list (one triangle), b_i g_c summed in list order into dst[3][C].
-__device__ __forceinline__ void ib_record(const float *vals, int S, int C, const FragLists &fl, int64_t base,
+// frag: the tile's sorted fragment list (in global memory or an LDS copy)
+__device__ __forceinline__ void ib_record(const float *vals, int S, int C, const uint16_t *frag,
                                           int j0, int j1, float *__restrict__ dst) {
     for (int c0 = 0; c0 < C; c0 += IB_CH) {
         float acc[3][IB_CH];
@@ -98,7 +99,7 @@ __device__ __forceinline__ void ib_record(const float *vals, int S, int C, const
 #pragma unroll
             for (int c = 0; c < IB_CH; c++) acc[i][c] = 0.0f;
         for (int j = j0; j < j1; j++) {
-            const float *v = vals + (int)fl.frag[base + j] * S;
+            const float *v = vals + (int)frag[j] * S;
             float w0 = v[0], w1 = v[1], w2 = 1.0f - w0 - w1;
 #pragma unroll
             for (int c = 0; c < IB_CH; c++) {

@@ -1585,11 +1585,21 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX) __attribute__((amdgpu_waves_p
     extern __shared__ float vals[];   // [256][ib_stride(CC)] interpolation rows, then [256][9]
     constexpr int S = (CC + 2) | 1;
     float *rvals = vals + DRESSI_TILE_PIX * S;
+    __shared__ uint16_t sfrag[DRESSI_TILE_PIX];   // the tile's sorted fragment list
     const int bt = (int)blockIdx.x;
     const int tx = bt % ntx, ty = bt / ntx;
     const int p = threadIdx.x;
     const int x = tx * DRESSI_TILE + (p & (DRESSI_TILE - 1));
     const int y = ty * DRESSI_TILE + p / DRESSI_TILE;
+    // the tile's lists are read before the fragments' adjoints, not after
+    // the barrier (in bounds whatever the counts: a tile has 256 slots of
+    // each; entries past the counts are never used)
+    const int64_t base = (int64_t)bt * DRESSI_TILE_PIX;
+    const int nf = fl.n_frag[bt];
+    const int nr = fl.n_rec[bt];
+    sfrag[p] = fl.frag[base + p];
+    const int rs0 = fl.rec_start[base + p];
+    const int rs1 = p + 1 < DRESSI_TILE_PIX ? fl.rec_start[base + p + 1] : 0;
     if (x < W && y < H) {
         const int64_t o = (int64_t)y * W + x;
         const int t = tri_id[o];
@@ -1613,18 +1623,17 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX) __attribute__((amdgpu_waves_p
         }
     }
     __syncthreads();
-    const int nf = fl.n_frag[bt];
-    const int nr = fl.n_rec[bt];
-    const int64_t base = (int64_t)bt * DRESSI_TILE_PIX;
-    for (int r = p; r < nr; r += DRESSI_TILE_PIX) {
-        const int j0 = fl.rec_start[base + r];
-        const int j1 = (r + 1 < nr) ? fl.rec_start[base + r + 1] : nf;
-        ib_record(vals, S, CC, fl, base, j0, j1, ipart + (base + r) * 3 * CC);
+    // one record per lane (a tile has at most 256)
+    if (p < nr) {
+        const int r = p;
+        const int j0 = rs0;
+        const int j1 = (r + 1 < nr) ? rs1 : nf;
+        ib_record(vals, S, CC, sfrag, j0, j1, ipart + (base + r) * 3 * CC);
         float acc9[9];
 #pragma unroll
         for (int c = 0; c < 9; c++) acc9[c] = 0.0f;
         for (int j = j0; j < j1; j++) {
-            const float *v = rvals + (int)fl.frag[base + j] * 9;
+            const float *v = rvals + (int)sfrag[j] * 9;
 #pragma unroll
             for (int c = 0; c < 9; c++) acc9[c] += v[c];
         }

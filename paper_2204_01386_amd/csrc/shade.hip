@@ -310,34 +310,57 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
     for (int c = 0; c < CC; c++) s[c] = 0.0f;
     float gx = 0.0f, gy = 0.0f, gw = 0.0f;
+    dbl3 nacc{0.0, 0.0, 0.0};
+    // one view: the transform's matrix is read before the walk rather than
+    // after it (uniform: scalar registers)
+    float M[16];
+    if (!vert_view) {
+#pragma unroll
+        for (int k = 0; k < 16; k++) M[k] = mvp[k];
+    }
     if (live) {
         const int j0 = adj.offsets[v], j1 = adj.offsets[v + 1];
-        if (lane < 4) {
-            for (int j = j0 + lane; j < j1; j += 4) {
-                const int cr = adj.corners[j];
-                const int t = cr / 3, i = cr - 3 * t;
-                float a[CC];
-#pragma unroll
-                for (int c = 0; c < CC; c++) a[c] = 0.0f;
-                for (int e = tt.offsets[t]; e < tt.offsets[t + 1]; e++) {
-                    const int2 ent = tt.entries[e];
-                    const float *pp = ipart + ((int64_t)ent.x * DRESSI_TILE_PIX + ent.y) * 3 * CC + i * CC;
-#pragma unroll
-                    for (int c = 0; c < CC; c++) a[c] += pp[c];
-                }
-#pragma unroll
-                for (int c = 0; c < CC; c++) s[c] += a[c];
-            }
-        }
         const float4 p = pos_clip[v];
         const double iw = 1.0 / (double)p.w, xn = (double)(p.x / p.w), yn = (double)(p.y / p.w);
+        // One walk for all three sums, so that their loads overlap.  Lane L
+        // takes the corners L, L + 8, ... for the clip-space gradient and the
+        // normal sum; lanes 0-3 also take the corners L, L + 4, L + 8, ... for
+        // the attribute gradient, here as the pairs (j, j + 4) of each step:
+        // every sum sees its terms in the order of its own kernel.
         for (int j = j0 + lane; j < j1; j += GV_LANES) {
             const int c = adj.corners[j];
             const int t = c / 3, i = c - 3 * t;
+            const bool two = lane < 4 && j + 4 < j1;
+            const int c2 = two ? adj.corners[j + 4] : c;
+            const int t2 = c2 / 3, i2 = c2 - 3 * t2;
+            const int e0 = tt.offsets[t], e1 = tt.offsets[t + 1];
+            const dbl3 f = face_normal_d(pos, tris, t, V);
+            nacc.x += f.x;
+            nacc.y += f.y;
+            nacc.z += f.z;
+            if (lane < 4) {
+#pragma unroll
+                for (int h = 0; h < 2; h++) {
+                    if (h == 1 && !two) break;
+                    const int ih = h ? i2 : i;
+                    const int f0 = h ? tt.offsets[t2] : e0, f1 = h ? tt.offsets[t2 + 1] : e1;
+                    float a[CC];
+#pragma unroll
+                    for (int q = 0; q < CC; q++) a[q] = 0.0f;
+                    for (int e = f0; e < f1; e++) {
+                        const int2 ent = tt.entries[e];
+                        const float *pp = ipart + ((int64_t)ent.x * DRESSI_TILE_PIX + ent.y) * 3 * CC + ih * CC;
+#pragma unroll
+                        for (int q = 0; q < CC; q++) a[q] += pp[q];
+                    }
+#pragma unroll
+                    for (int q = 0; q < CC; q++) s[q] += a[q];
+                }
+            }
             // a triangle without fragments adds nothing (as in k_rast_bwd_vertex)
-            if (tt.offsets[t] == tt.offsets[t + 1]) continue;
+            if (e0 == e1) continue;
             double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-            for (int e = tt.offsets[t]; e < tt.offsets[t + 1]; e++) {
+            for (int e = e0; e < e1; e++) {
                 const int2 ent = tt.entries[e];
                 const float *r = rpart + ((int64_t)ent.x * DRESSI_TILE_PIX + ent.y) * 9 + 3 * i;
                 a0 += (double)r[0];
@@ -361,14 +384,21 @@ __global__ void __launch_bounds__(256)
         gx += __shfl_xor(gx, m, 64);
         gy += __shfl_xor(gy, m, 64);
         gw += __shfl_xor(gw, m, 64);
+        // the normal sum's butterfly, as in vertex_acc
+        nacc.x += __shfl_xor(nacc.x, m, 64);
+        nacc.y += __shfl_xor(nacc.y, m, 64);
+        nacc.z += __shfl_xor(nacc.z, m, 64);
     }
-    const dbl3 nacc = vertex_acc(pos, tris, adj, (int)v, V, live, lane);
     if (!live || lane != 0) return;
 #pragma unroll
     for (int c = 0; c < CC; c++) grad_attr[v * CC + c] = s[c];
     const float4 q = make_float4(gx, gy, 0.0f, gw);
     grad_pos_clip[v] = q;
-    const float *M = mvp + 16 * (int64_t)(vert_view ? vert_view[v] : 0);
+    if (vert_view) {
+        const float *Mp = mvp + 16 * (int64_t)vert_view[v];
+#pragma unroll
+        for (int k = 0; k < 16; k++) M[k] = Mp[k];
+    }
     float hx = 0.0f, hy = 0.0f, hz = 0.0f;
     hx += M[0] * q.x + M[4] * q.y + M[8] * q.z + M[12] * q.w;
     hy += M[1] * q.x + M[5] * q.y + M[9] * q.z + M[13] * q.w;
