@@ -181,6 +181,7 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX)
                       const float *__restrict__ grad_out, const float2 *__restrict__ gb_in,
                       float2 *__restrict__ grad_bary, float *__restrict__ partial, int skip_empty) {
     extern __shared__ float vals[];   // [K*256][ib_stride(C)]
+    __shared__ uint16_t sfrag[DRESSI_MAX_K * DRESSI_TILE_PIX];   // the tile's sorted fragment list
     if (CC > 0) C = CC;
     // several views: XCD-aware order (each XCD whole views); one view keeps the
     // default interleave, which balances uneven work over the image
@@ -188,6 +189,15 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX)
     const int b = bt / nt, tile = bt - b * nt;
     const int tx = tile % ntx, ty = tile / ntx;
     const int p = threadIdx.x;
+    // the tile's lists are read before the fragments' adjoints, not after
+    // the barrier (in bounds whatever the counts: K*256 slots each)
+    const int64_t base = (int64_t)bt * DRESSI_TILE_PIX * K;
+    const int nf = fl.n_frag[bt];
+    const int nr = fl.n_rec[bt];
+    const int np = K * DRESSI_TILE_PIX;
+    for (int i = p; i < np; i += DRESSI_TILE_PIX) sfrag[i] = fl.frag[base + i];
+    const int rs0 = fl.rec_start[base + p];
+    const int rs1 = p + 1 < np ? fl.rec_start[base + p + 1] : 0;
     const int x = tx * DRESSI_TILE + (p & (DRESSI_TILE - 1));
     const int y = ty * DRESSI_TILE + p / DRESSI_TILE;
     const int S = ib_stride(C);
@@ -201,13 +211,10 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX)
         }
     }
     __syncthreads();
-    const int nf = fl.n_frag[bt];
-    const int nr = fl.n_rec[bt];
-    const int64_t base = (int64_t)bt * DRESSI_TILE_PIX * K;
     for (int r = p; r < nr; r += DRESSI_TILE_PIX) {
-        int j0 = fl.rec_start[base + r];
-        int j1 = (r + 1 < nr) ? fl.rec_start[base + r + 1] : nf;
-        ib_record(vals, S, C, fl.frag + base, j0, j1, partial + (base + r) * 3 * C);
+        const int j0 = r == p ? rs0 : fl.rec_start[base + r];
+        const int j1 = (r + 1 < nr) ? (r == p ? rs1 : fl.rec_start[base + r + 1]) : nf;
+        ib_record(vals, S, C, sfrag, j0, j1, partial + (base + r) * 3 * C);
     }
 }
 

@@ -1373,6 +1373,7 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX)
                     FragLists fl, int ntx, int nt, const float2 *__restrict__ grad_bary,
                     const float *__restrict__ grad_dist, float *__restrict__ partial) {
     extern __shared__ float vals[];   // [K*256][9]
+    __shared__ uint16_t sfrag[DRESSI_MAX_K * DRESSI_TILE_PIX];   // the tile's sorted fragment list
     // several views: XCD-aware order (each XCD whole views); one view keeps the
     // default interleave, which balances uneven work over the image
     const int bt = (int)gridDim.x > nt ? (int)xcd_block() : (int)blockIdx.x;
@@ -1381,6 +1382,12 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX)
     const int b = bt / nt, tile = bt - b * nt;
     const int tx = tile % ntx, ty = tile / ntx;
     const int p = threadIdx.x;
+    // the tile's sorted list is read before the fragments' gradients, not
+    // after the barrier (in bounds whatever the count: K*256 slots)
+    const int64_t base = (int64_t)bt * DRESSI_TILE_PIX * K;
+    const int nr = fl.n_rec[bt];
+    const int np = K * DRESSI_TILE_PIX;
+    for (int i = p; i < np; i += DRESSI_TILE_PIX) sfrag[i] = fl.frag[base + i];
     const int x = tx * DRESSI_TILE + (p & (DRESSI_TILE - 1));
     const int y = ty * DRESSI_TILE + p / DRESSI_TILE;
     const float4 *pc = pos_clip + (int64_t)b * V;
@@ -1406,16 +1413,14 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX)
         }
     }
     __syncthreads();
-    const int64_t base = (int64_t)bt * DRESSI_TILE_PIX * K;
-    const int nr = fl.n_rec[bt];
     for (int r = p; r < nr; r += DRESSI_TILE_PIX) {
-        int j0 = fl.rec_start[base + r];
-        int j1 = (r + 1 < nr) ? fl.rec_start[base + r + 1] : nf;
+        const int j0 = fl.rec_start[base + r];
+        const int j1 = (r + 1 < nr) ? fl.rec_start[base + r + 1] : nf;
         float acc[9];
 #pragma unroll
         for (int c = 0; c < 9; c++) acc[c] = 0.0f;
         for (int j = j0; j < j1; j++) {
-            const float *v = vals + (int)fl.frag[base + j] * 9;
+            const float *v = vals + (int)sfrag[j] * 9;
 #pragma unroll
             for (int c = 0; c < 9; c++) acc[c] += v[c];
         }
