@@ -966,28 +966,36 @@ extern "C" int dressi_rasterize_batched(dressi_ctx *ctx, const float *pos_clip, 
 // ---------------------------------------------------------------------------
 // per-tile fragment lists sorted by triangle id
 // ---------------------------------------------------------------------------
-// Sort keys are (triangle id << 11 | local fragment k*256 + pixel); an empty
-// slot gets FS_SENT | local, above every fragment key.  All keys of a tile are
-// distinct, so a key's rank is its sorted position.
-#define FS_SENT 0xfffffffffffff800ull
-
-__device__ __forceinline__ unsigned long long shfl_xor_u64(unsigned long long v, int m) {
-    const unsigned lo = __shfl_xor((unsigned)(v & 0xffffffffu), m, 64);
-    const unsigned hi = __shfl_xor((unsigned)(v >> 32), m, 64);
-    return ((unsigned long long)hi << 32) | lo;
+// Sort keys are (triangle id << EB | local fragment k*256 + pixel), EB = 8
+// for one layer and 11 for up to five; an empty slot gets the sentinel bits
+// (all ones above EB) | local, above every fragment key.  The keys are 32-bit
+// when the triangle count leaves room (T < 2^(32 - EB) - 1), else 64-bit:
+// the same order either way.  All keys of a tile are distinct, so a key's
+// rank is its sorted position.  A triangle id >= T (never written by the
+// rasterizer) is recorded as T, which every consumer skips.
+template <typename KT>
+__device__ __forceinline__ KT shfl_xor_key(KT v, int m) {
+    if constexpr (sizeof(KT) == 4) {
+        return (KT)__shfl_xor((unsigned)v, m, 64);
+    } else {
+        const unsigned lo = __shfl_xor((unsigned)(v & 0xffffffffu), m, 64);
+        const unsigned hi = __shfl_xor((unsigned)(v >> 32), m, 64);
+        return ((KT)hi << 32) | lo;
+    }
 }
 
 // bitonic sort of one key per lane across a wavefront, ascending in lane order
-__device__ __forceinline__ unsigned long long wave_sort_u64(unsigned long long v) {
+template <typename KT>
+__device__ __forceinline__ KT wave_sort_key(KT v) {
     const int lane = threadIdx.x & 63;
 #pragma unroll
     for (int k = 2; k <= 64; k <<= 1) {
 #pragma unroll
         for (int j = k >> 1; j > 0; j >>= 1) {
-            const unsigned long long o = shfl_xor_u64(v, j);
+            const KT o = shfl_xor_key(v, j);
             const bool up = (lane & k) == 0;   // this lane's block sorts ascending
             const bool low = (lane & j) == 0;
-            const unsigned long long mn = v < o ? v : o, mx = v < o ? o : v;
+            const KT mn = v < o ? v : o, mx = v < o ? o : v;
             v = (low == up) ? mn : mx;
         }
     }
@@ -995,7 +1003,8 @@ __device__ __forceinline__ unsigned long long wave_sort_u64(unsigned long long v
 }
 
 // number of keys below v in a sorted run of 64
-__device__ __forceinline__ int run_rank(const unsigned long long *run, unsigned long long v) {
+template <typename KT>
+__device__ __forceinline__ int run_rank(const KT *run, KT v) {
     int lo = 0;
 #pragma unroll
     for (int s = 32; s >= 1; s >>= 1)
@@ -1008,13 +1017,17 @@ __device__ __forceinline__ int run_rank(const unsigned long long *run, unsigned 
 // wavefront each, in registers), every key is placed at its rank (its index in
 // its run plus its rank in each other run), and the sorted list is cut into
 // per-triangle records.
+template <typename KT, int EB>
 __global__ void __launch_bounds__(DRESSI_TILE_PIX)
     k_fragsort(const int32_t *__restrict__ tri_id, int K, int H, int W, int ntx, int nt, int T,
                int32_t *__restrict__ n_frag, int32_t *__restrict__ n_rec, uint16_t *__restrict__ frag,
                int32_t *__restrict__ rec_tri, int32_t *__restrict__ rec_start,
                int32_t *__restrict__ tri_counts) {
-    __shared__ unsigned long long runs[DRESSI_MAX_K * DRESSI_TILE_PIX];
-    __shared__ unsigned long long keys[DRESSI_MAX_K * DRESSI_TILE_PIX];
+    constexpr KT SENT = (KT)(~(KT)0) << EB;
+    constexpr unsigned EMASK = (1u << EB) - 1u;
+    constexpr int KMAX = EB == 8 ? 1 : DRESSI_MAX_K;
+    __shared__ KT runs[KMAX * DRESSI_TILE_PIX];
+    __shared__ KT keys[KMAX * DRESSI_TILE_PIX];
     __shared__ int wsum[DRESSI_TILE_PIX / 64];
     // several views: XCD-aware order (each XCD whole views); one view keeps the
     // default interleave, which balances uneven work over the image
@@ -1026,15 +1039,15 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX)
     const int y = ty * DRESSI_TILE + p / DRESSI_TILE;
     const int np = K * DRESSI_TILE_PIX, nruns = np / 64;
     int any = 0;
-    unsigned long long kv[DRESSI_MAX_K];
+    KT kv[KMAX];
 #pragma unroll
-    for (int k = 0; k < DRESSI_MAX_K; k++) {
+    for (int k = 0; k < KMAX; k++) {
         const int e = k * DRESSI_TILE_PIX + p;
-        kv[k] = FS_SENT | (unsigned long long)e;
+        kv[k] = SENT | (KT)e;
         if (k < K && x < W && y < H) {
             const int t = tri_id[(((int64_t)b * K + k) * H + y) * W + x];
             if (t >= 0) {
-                kv[k] = ((unsigned long long)t << 11) | (unsigned long long)e;
+                kv[k] = ((KT)(t < T ? t : T) << EB) | (KT)e;
                 any = 1;
             }
         }
@@ -1047,13 +1060,13 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX)
         return;
     }
 #pragma unroll
-    for (int k = 0; k < DRESSI_MAX_K; k++)
-        if (k < K) runs[k * DRESSI_TILE_PIX + p] = wave_sort_u64(kv[k]);   // run = this wavefront's layer-k keys
+    for (int k = 0; k < KMAX; k++)
+        if (k < K) runs[k * DRESSI_TILE_PIX + p] = wave_sort_key(kv[k]);   // run = this wavefront's layer-k keys
     __syncthreads();
     for (int k = 0; k < K; k++) {
         const int e = k * DRESSI_TILE_PIX + p;
         const int run = e >> 6;
-        const unsigned long long v = runs[e];
+        const KT v = runs[e];
         int pos = e & 63;
         for (int r2 = 0; r2 < nruns; r2++)
             if (r2 != run) pos += run_rank(runs + r2 * 64, v);
@@ -1065,10 +1078,10 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX)
     const int i0 = p * per;
     int heads = 0, valid = 0;
     for (int j = 0; j < per; j++) {
-        unsigned long long kv = keys[i0 + j];
-        if (kv >= FS_SENT) break;
+        const KT kv = keys[i0 + j];
+        if (kv >= SENT) break;
         valid++;
-        if (i0 + j == 0 || (keys[i0 + j - 1] >> 11) != (kv >> 11)) heads++;
+        if (i0 + j == 0 || (keys[i0 + j - 1] >> EB) != (kv >> EB)) heads++;
     }
     int total_heads;
     int rbase;
@@ -1092,11 +1105,11 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX)
     int r = rbase;
     for (int j = 0; j < per; j++) {
         int i = i0 + j;
-        unsigned long long kv = keys[i];
-        if (kv >= FS_SENT) break;
-        frag[base + i] = (uint16_t)(kv & 2047u);
-        if (i == 0 || (keys[i - 1] >> 11) != (kv >> 11)) {
-            int t = (int)(kv >> 11);
+        const KT kv = keys[i];
+        if (kv >= SENT) break;
+        frag[base + i] = (uint16_t)(kv & EMASK);
+        if (i == 0 || (keys[i - 1] >> EB) != (kv >> EB)) {
+            int t = (int)(kv >> EB);
             rec_tri[base + r] = t;
             rec_start[base + r] = i;
             if (t < T) atomicAdd(&tri_counts[(int64_t)b * T + t], 1);
@@ -1106,7 +1119,7 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX)
     // number of valid keys = position of the first sentinel (keys are sorted)
     if (valid < per) {
         int i = i0 + valid;
-        if (i == 0 || keys[i - 1] < FS_SENT) n_frag[bt] = i;
+        if (i == 0 || keys[i - 1] < SENT) n_frag[bt] = i;
     } else if (p == DRESSI_TILE_PIX - 1) {
         n_frag[bt] = np;
     }
@@ -1199,9 +1212,18 @@ void dressi_build_fragindex(const int32_t *tri_id, int B, int K, int H, int W, i
     TriTiles tt;
     dressi_fragindex_view(base, B, K, H, W, T, fl, tt);
     int ntx = tiles_x(W), nt = ntx * tiles_y(H);
-    if (B * nt > 0)
-        DR_LAUNCH("k_fragsort", (k_fragsort), B * nt, DRESSI_TILE_PIX, 0, s, tri_id, K, H, W, ntx, nt, T,
-                  fl.n_frag, fl.n_rec, fl.frag, fl.rec_tri, fl.rec_start, counts);
+    if (B * nt > 0) {
+        // 32-bit keys while the triangle ids leave room above the local index
+        if (K == 1 && T < (1 << 24) - 1)
+            DR_LAUNCH("k_fragsort", (k_fragsort<uint32_t, 8>), B * nt, DRESSI_TILE_PIX, 0, s, tri_id, K, H, W, ntx,
+                      nt, T, fl.n_frag, fl.n_rec, fl.frag, fl.rec_tri, fl.rec_start, counts);
+        else if (T < (1 << 21) - 1)
+            DR_LAUNCH("k_fragsort", (k_fragsort<uint32_t, 11>), B * nt, DRESSI_TILE_PIX, 0, s, tri_id, K, H, W, ntx,
+                      nt, T, fl.n_frag, fl.n_rec, fl.frag, fl.rec_tri, fl.rec_start, counts);
+        else
+            DR_LAUNCH("k_fragsort", (k_fragsort<unsigned long long, 11>), B * nt, DRESSI_TILE_PIX, 0, s, tri_id, K,
+                      H, W, ntx, nt, T, fl.n_frag, fl.n_rec, fl.frag, fl.rec_tri, fl.rec_start, counts);
+    }
     int64_t n = (int64_t)B * T;
     dressi_exclusive_scan(counts, tt.offsets, n, tmp, s);
     int2 *unsorted = reinterpret_cast<int2 *>(static_cast<char *>(tmp) +
