@@ -129,8 +129,10 @@ int dressi_check_status(dressi_ctx *ctx, int64_t *needed, void *stream);
  *   triangle-parallel per tile with LDS atomics (small triangles), 1 =
  *   pixel-parallel with per-pixel lists in registers (large triangles), 2 =
  *   chosen per tile and batch of 256 binned triangles from their on-tile
- *   extents (K = 1; with K > 1 it acts as 1).  All select exactly the same
- *   layers;
+ *   extents (K = 1; with K > 1 it acts as 1), 3 = without bins: one lane per
+ *   triangle merges its keys into a per-pixel array with global atomics,
+ *   then each pixel is resolved (K = 1; with K > 1 it acts as 0; small
+ *   triangles).  All select exactly the same layers;
  * DRESSI_TUNE_HYBRID_WEIGHT: for strategy 2, the cost of a pixel-parallel
  *   triangle step relative to a triangle-parallel pixel step, in sixteenths
  *   (1..1024, default 24).

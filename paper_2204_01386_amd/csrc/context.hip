@@ -128,7 +128,7 @@ extern "C" int dressi_tune(dressi_ctx *ctx, int key, int64_t value) {
         ctx->bin_capacity = value;   // 0 = automatic
         return DRESSI_OK;
     case DRESSI_TUNE_HARD_RASTER:
-        if (value < 0 || value > 2) return dressi_fail(ctx, DRESSI_EINVAL, "tune: hard raster is 0, 1 or 2");
+        if (value < 0 || value > 3) return dressi_fail(ctx, DRESSI_EINVAL, "tune: hard raster is 0, 1, 2 or 3");
         ctx->hard_raster = (int)value;
         return DRESSI_OK;
     case DRESSI_TUNE_HYBRID_WEIGHT:

@@ -166,9 +166,35 @@ __device__ __forceinline__ void raster_tri_in_tile(const TriSetup &s, int t, int
     }
 }
 
-// Writes the K layers of one pixel: triangle id, perspective-correct (b0, b1)
-// and, for soft rasterization, the signed normalised distance (+ for a hard
-// fragment, - for a soft one).
+// One fragment of triangle t (set up as s) at pixel centre (px, py):
+// triangle id, perspective-correct (b0, b1) and, for soft rasterization, the
+// signed normalised distance (+ for a hard fragment, - for a soft one).
+template <bool SOFT>
+__device__ __forceinline__ void resolve_frag(const TriSetup &s, int t, int px, int py, float key, float dscale,
+                                             int64_t o, int32_t *__restrict__ tri_id, float2 *__restrict__ bary,
+                                             float *__restrict__ dist) {
+    double E[3];
+#pragma unroll
+    for (int i = 0; i < 3; i++) E[i] = dr_edge(s.X, s.Y, i, px, py);
+    // perspective-correct b_i = (l_i / w_i) / sum_j (l_j / w_j) with
+    // l_i = E_i / 2A: the area cancels, and multiplying through by
+    // w0 w1 w2 leaves one division.  In double: soft fragments
+    // extrapolate and the sum can come close to zero for grazing triangles.
+    const double w0 = s.w[0], w1 = s.w[1], w2 = s.w[2];
+    const double q0 = E[0] * (w1 * w2), q1 = E[1] * (w0 * w2), q2 = E[2] * (w0 * w1);
+    const double iQ = 1.0 / (q0 + q1 + q2);
+    double b0 = q0 * iQ, b1 = q1 * iQ, b2 = q2 * iQ;
+    bool swapped = dr_corner(s.meta, 1) == 2;
+    tri_id[o] = t;
+    bary[o] = make_float2((float)b0, (float)(swapped ? b2 : b1));
+    if (SOFT) {
+        int ne;
+        float dn = dr_distnorm(s.X, s.Y, px, py, E, dscale, ne);
+        dist[o] = key < 0.5f ? dn : -dn;
+    }
+}
+
+// Writes the K layers of one pixel (resolve_frag for each found layer).
 template <int K, bool SOFT>
 __device__ __forceinline__ void resolve_store(const TriSetup *__restrict__ sv, const float *key,
                                               const int *id, int b, int x, int y, int px, int py,
@@ -185,26 +211,7 @@ __device__ __forceinline__ void resolve_store(const TriSetup *__restrict__ sv, c
             if (SOFT) dist[o] = 0.0f;
             continue;
         }
-        TriSetup s = sv[t];
-        double E[3];
-#pragma unroll
-        for (int i = 0; i < 3; i++) E[i] = dr_edge(s.X, s.Y, i, px, py);
-        // perspective-correct b_i = (l_i / w_i) / sum_j (l_j / w_j) with
-        // l_i = E_i / 2A: the area cancels, and multiplying through by
-        // w0 w1 w2 leaves one division.  In double: soft fragments
-        // extrapolate and the sum can come close to zero for grazing triangles.
-        const double w0 = s.w[0], w1 = s.w[1], w2 = s.w[2];
-        const double q0 = E[0] * (w1 * w2), q1 = E[1] * (w0 * w2), q2 = E[2] * (w0 * w1);
-        const double iQ = 1.0 / (q0 + q1 + q2);
-        double b0 = q0 * iQ, b1 = q1 * iQ, b2 = q2 * iQ;
-        bool swapped = dr_corner(s.meta, 1) == 2;
-        tri_id[o] = t;
-        bary[o] = make_float2((float)b0, (float)(swapped ? b2 : b1));
-        if (SOFT) {
-            int ne;
-            float dn = dr_distnorm(s.X, s.Y, px, py, E, dscale, ne);
-            dist[o] = key[k] < 0.5f ? dn : -dn;
-        }
+        resolve_frag<SOFT>(sv[t], t, px, py, key[k], dscale, o, tri_id, bary, dist);
     }
 }
 
@@ -786,6 +793,82 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX) __attribute__((amdgpu_waves_p
     }
 }
 
+// Hard single-layer rasterization without bins (strategy 3, K = 1): one lane
+// per (view, triangle) sets the triangle up as k_setup_bin does and merges
+// its key (depth bits << 32 | id, as k_raster) into every covered pixel of its
+// box with a 64-bit global atomicMax of the key's complement, on a per-pixel
+// array kept at zero between calls (zero: no fragment); a second kernel
+// resolves each pixel from the surviving key, recomputing the winner's setup,
+// and sets the entry back to zero.  The smallest key and the smallest id at
+// it, whatever the order of the atomics: the layer the other strategies
+// select.  A lane's work is its triangle's box, so this suits small
+// triangles; the autotuner times it against the others.
+__device__ __forceinline__ bool direct_setup(const float4 *__restrict__ pos_clip, const int32_t *__restrict__ tris,
+                                             const Viewports &vp, int b, int V, int t, int H, int W, int cull,
+                                             TriSetup &s) {
+    const int32_t *tv = tris + 3 * (int64_t)t;
+    const int v0 = tv[0], v1 = tv[1], v2 = tv[2];
+    if (v0 < 0 || v0 >= V || v1 < 0 || v1 >= V || v2 < 0 || v2 >= V) return false;
+    const int4 q = dr_viewport(vp, t, H, W);
+    s = dr_setup(pos_clip + (int64_t)b * V, v0, v1, v2, q.w, q.z, q.x, q.y, cull, 0);
+    return (s.meta & 1) != 0;
+}
+
+__global__ void k_raster_direct(const float4 *__restrict__ pos_clip, const int32_t *__restrict__ tris, Viewports vp,
+                                int B, int V, int T, int H, int W, int cull, unsigned long long *__restrict__ zbuf) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= (int64_t)B * T) return;
+    const int b = (int)(gid / T), t = (int)(gid - (int64_t)b * T);
+    TriSetup s;
+    if (!direct_setup(pos_clip, tris, vp, b, V, t, H, W, cull, s)) return;
+    const int x0 = s.box0 & 0xffff, x1 = s.box0 >> 16, y0 = s.box1 & 0xffff, y1 = s.box1 >> 16;
+    unsigned long long *zb = zbuf + (int64_t)b * H * W;
+    for (int y = y0; y <= y1; y++) {
+        const int py = DRESSI_SUBPIX * y + DRESSI_SUBPIX / 2;
+        for (int x = x0; x <= x1; x++) {
+            const int px = DRESSI_SUBPIX * x + DRESSI_SUBPIX / 2;
+            double E[3];
+            bool in = true;
+#pragma unroll
+            for (int i = 0; i < 3; i++) {
+                E[i] = dr_edge(s.X, s.Y, i, px, py);
+                bool own = (s.meta >> (1 + i)) & 1;
+                in = in && (E[i] > 0 || (E[i] == 0 && own));
+            }
+            if (!in) continue;
+            const float z = dr_depth(s, E);
+            if (!(z > 0.0f && z < 1.0f)) continue;
+            const unsigned long long v = ((unsigned long long)__float_as_uint(0.5f * z) << 32) | (unsigned)t;
+            atomicMax(&zb[(int64_t)y * W + x], ~v);
+        }
+    }
+}
+
+__global__ void k_raster_direct_resolve(const float4 *__restrict__ pos_clip, const int32_t *__restrict__ tris,
+                                        Viewports vp, int B, int V, int T, int H, int W, int cull,
+                                        unsigned long long *__restrict__ zbuf, int32_t *__restrict__ tri_id,
+                                        float2 *__restrict__ bary) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t npix = (int64_t)H * W;
+    if (i >= (int64_t)B * npix) return;
+    const unsigned long long c = zbuf[i];
+    if (c == 0ull) {   // no fragment
+        tri_id[i] = -1;
+        bary[i] = make_float2(0.0f, 0.0f);
+        return;
+    }
+    zbuf[i] = 0ull;
+    const unsigned long long v = ~c;
+    const int t = (int)(v & 0xffffffffu);
+    const int b = (int)(i / npix);
+    const int64_t pix = i - (int64_t)b * npix;
+    const int y = (int)(pix / W), x = (int)(pix - (int64_t)y * W);
+    TriSetup s;
+    direct_setup(pos_clip, tris, vp, b, V, t, H, W, cull, s);   // valid: it produced the key
+    resolve_frag<false>(s, t, DRESSI_SUBPIX * x + DRESSI_SUBPIX / 2, DRESSI_SUBPIX * y + DRESSI_SUBPIX / 2,
+                        __uint_as_float((unsigned)(v >> 32)), 0.0f, i, tri_id, bary, nullptr);
+}
+
 // Hard rasterization has two strategies with identical results (the layer
 // selection does not depend on visiting order): triangle-parallel per tile
 // with LDS atomics (small triangles) or pixel-parallel with register lists
@@ -800,7 +883,7 @@ static void launch_raster_k(bool soft, int hard_pix, int hyb_w, dim3 g, hipStrea
     else if (hard_pix == 2 && K == 1)
         DR_LAUNCH("k_raster_list", (k_raster_list<1, false, true>), g, DRESSI_TILE_PIX, 0, st, setup, counts,
                   bins, cap, T, H, W, ntx, nt, r, tid, bary, dist, hyb_w, nullptr, 0);
-    else if (hard_pix)
+    else if (hard_pix == 1 || hard_pix == 2)
         DR_LAUNCH("k_raster_list", (k_raster_list<K, false>), g, DRESSI_TILE_PIX, 0, st, setup, counts, bins,
                   cap, T, H, W, ntx, nt, r, tid, bary, dist, 0, nullptr, 0);
     else
@@ -859,6 +942,21 @@ static int rasterize_impl(dressi_ctx *ctx, const float *pos_clip, const int32_t 
     if (soft && !dist) return dressi_fail(ctx, DRESSI_EINVAL, "rasterize: dist is required when r > 0");
     if (B == 0) return DRESSI_OK;
     hipStream_t st = (hipStream_t)stream;
+    if (!soft && K == 1 && ctx->hard_raster == 3) {
+        // binless (strategy 3): a per-pixel key array in the zeroed counters
+        const int64_t npx = (int64_t)B * H * W;
+        rc = dressi_counters(ctx, (size_t)(2 * npx), st);
+        if (rc) return rc;
+        unsigned long long *zbuf = reinterpret_cast<unsigned long long *>(ctx->counters);
+        const float4 *pc4 = reinterpret_cast<const float4 *>(pos_clip);
+        const int64_t ntri = (int64_t)B * T;
+        if (ntri > 0)
+            DR_LAUNCH("k_raster_direct", (k_raster_direct), (int)((ntri + 255) / 256), 256, 0, st, pc4, tris, vp, B,
+                      V, T, H, W, cull, zbuf);
+        DR_LAUNCH("k_raster_direct_resolve", (k_raster_direct_resolve), (int)((npx + 255) / 256), 256, 0, st, pc4,
+                  tris, vp, B, V, T, H, W, cull, zbuf, tri_id, reinterpret_cast<float2 *>(bary));
+        return dressi_launch_check(ctx, "rasterize");
+    }
     int ntx = tiles_x(W), nty = tiles_y(H), nt = ntx * nty;
     int margin = soft_margin(r, W);
     int cap = tile_capacity(ctx, B, T, nt, margin);
@@ -1792,7 +1890,9 @@ extern "C" int dressi_reserve_limits(dressi_ctx *ctx, const dressi_limits *l) {
     int rc = dressi_reserve(ctx, bytes, cap);
     if (rc) return rc;
     const size_t nt = (size_t)tiles_x(l->W) * tiles_y(l->H);
-    const size_t nc = std::max((size_t)std::max(l->B, 1) * nt, (size_t)std::max(l->B, 1) * std::max(l->T, 0));
+    size_t nc = std::max((size_t)std::max(l->B, 1) * nt, (size_t)std::max(l->B, 1) * std::max(l->T, 0));
+    // one layer: the binless hard rasterizer's per-pixel keys (two counters a pixel)
+    if (l->K <= 1) nc = std::max(nc, 2 * (size_t)std::max(l->B, 1) * std::max(l->H, 0) * std::max(l->W, 0));
     return dressi_counters(ctx, nc, nullptr);
 }
 

@@ -1038,11 +1038,13 @@ def make_batch_target(scenes_list, device="cuda") -> BatchStep:
 # ---------------------------------------------------------------------------
 # autotuning
 # ---------------------------------------------------------------------------
-HARD_RASTER_NAMES = {None: "pixel-parallel (soft)", 0: "triangle-parallel", 1: "pixel-parallel", 2: "per-tile"}
+HARD_RASTER_NAMES = {None: "pixel-parallel (soft)", 0: "triangle-parallel", 1: "pixel-parallel", 2: "per-tile",
+                     3: "binless (global atomics)"}
 def autotune(step, reps: int = 5) -> dict:
     """Picks the hard-rasterization strategy (triangle-parallel tiles,
-    pixel-parallel tiles, or a choice per tile and triangle batch with one of
-    a few cost weights) and the tile-bin capacity for this step's own geometry
+    pixel-parallel tiles, a choice per tile and triangle batch with one of a
+    few cost weights, or, for one layer, triangle-parallel without bins) and
+    the tile-bin capacity for this step's own geometry
     by timing each candidate's transform + rasterization on the device, after
     checking that it selects exactly the same layers as the first candidate
     (it must: the choice changes speed only).  The choice is stored on the
@@ -1055,19 +1057,20 @@ def autotune(step, reps: int = 5) -> dict:
     else:
         cands = [(0, HYBRID_WEIGHT_DEFAULT), (1, HYBRID_WEIGHT_DEFAULT)]
         if getattr(step, "K", 1) == 1:
-            cands += [(2, w) for w in HYBRID_WEIGHTS]
+            cands += [(2, w) for w in HYBRID_WEIGHTS] + [(3, HYBRID_WEIGHT_DEFAULT)]
     need = 0
     results = {}
     ref = None
+    ref_bary = None
     for hr, w in cands:
         step.hard_raster, step.hybrid_weight = hr, w
         step._raster()
         torch.cuda.synchronize()
         need = max(need, ctx.check_status())
-        tid = step.tri_id.clone()
+        tid, bary = step.tri_id.clone(), step.bary.clone()
         if ref is None:
-            ref = tid
-        elif not torch.equal(ref, tid):
+            ref, ref_bary = tid, bary
+        elif not torch.equal(ref, tid) or not torch.equal(ref_bary[ref >= 0], bary[ref >= 0]):
             raise RuntimeError(f"rasterization strategy {hr} (weight {w}) selects different layers")
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()

@@ -120,12 +120,12 @@ def test_batch_deterministic_and_graph_replay(small_batch, concurrent):
 def test_autotune_strategies_give_identical_steps(small_batch):
     """Every hard-rasterization strategy (triangle-parallel, pixel-parallel,
     per tile and batch at several cost weights, the last with both extremes
-    that force one side everywhere) gives bitwise the same step; the
-    autotuner keeps the fastest."""
+    that force one side everywhere, and without bins) gives bitwise the same
+    step; the autotuner keeps the fastest."""
     from paper_2204_01386_amd.pipeline import autotune
     bs = _batched(small_batch)
     outs = []
-    for hr, w in ((0, 40), (1, 40), (2, 1), (2, 40), (2, 1024)):
+    for hr, w in ((0, 40), (1, 40), (2, 1), (2, 40), (2, 1024), (3, 24)):
         bs.hard_raster, bs.hybrid_weight = hr, w
         bs.run()
         torch.cuda.synchronize()
@@ -134,12 +134,12 @@ def test_autotune_strategies_give_identical_steps(small_batch):
         for a, b in zip(outs[0], o):
             assert np.array_equal(a, b)
     res = autotune(bs)
-    assert res["hard_raster"] in (0, 1, 2) and bs.hard_raster == res["hard_raster"]
+    assert res["hard_raster"] in (0, 1, 2, 3) and bs.hard_raster == res["hard_raster"]
     # a scene with large triangles on screen (few triangles, high resolution)
     big = scenes.config4(seed=5, n=3, t_min=200, t_max=400, sizes=(512,), tex_size=64)
     bs2 = _batched(big)
     ref = host(bs2.g_pos).copy()
-    for hr, w in ((1, 40), (2, 40), (2, 1024)):
+    for hr, w in ((1, 40), (2, 40), (2, 1024), (3, 24)):
         bs2.hard_raster, bs2.hybrid_weight = hr, w
         bs2.run()
         torch.cuda.synchronize()

@@ -226,11 +226,12 @@ def test_raster_banded_config3_full_size(B):
     assert np.array_equal(host(tid), tid_o)
 
 
-@pytest.mark.parametrize("hr,w", [(1, 40), (2, 1), (2, 40), (2, 1024)])
+@pytest.mark.parametrize("hr,w", [(1, 40), (2, 1), (2, 40), (2, 1024), (3, 24)])
 def test_raster_hard_strategies(B, hr, w):
     """Every hard-rasterization strategy selects exactly the oracle's layers:
-    pixel-parallel, and per tile and triangle batch (with weights that force
-    either side everywhere and the default mix).  Large on-screen triangles
+    pixel-parallel, per tile and triangle batch (with weights that force
+    either side everywhere and the default mix), and without bins (one layer;
+    with two it acts as the triangle-parallel strategy).  Large on-screen triangles
     (a coarse tiling, the K = 2 multi-layer case), small ones (the 81,920
     triangle sphere) and adversarial ones (shared edges, duplicates)."""
     ctx = B.context()
@@ -280,12 +281,13 @@ def test_tune_rejects_bad_values(B):
     """The tuning knobs accept only their documented ranges and leave the
     context usable (a rejected value changes nothing)."""
     ctx = B.Context(torch.cuda.current_device())
-    bad = [(B.TUNE_HARD_RASTER, -1), (B.TUNE_HARD_RASTER, 3), (B.TUNE_HYBRID_WEIGHT, 0),
+    bad = [(B.TUNE_HARD_RASTER, -1), (B.TUNE_HARD_RASTER, 4), (B.TUNE_HYBRID_WEIGHT, 0),
            (B.TUNE_HYBRID_WEIGHT, 1025), (B.TUNE_BIN_CAPACITY, -1), (B.TUNE_BIN_CAPACITY, (1 << 26) + 1), (99, 1)]
     for key, value in bad:
         with pytest.raises(B.DressiError, match="EINVAL"):
             ctx.tune(key, value)
-    for key, value in [(B.TUNE_HARD_RASTER, 2), (B.TUNE_HYBRID_WEIGHT, 1), (B.TUNE_HYBRID_WEIGHT, 1024),
+    for key, value in [(B.TUNE_HARD_RASTER, 3), (B.TUNE_HARD_RASTER, 2), (B.TUNE_HYBRID_WEIGHT, 1),
+                       (B.TUNE_HYBRID_WEIGHT, 1024),
                        (B.TUNE_BIN_CAPACITY, 0)]:
         ctx.tune(key, value)
 
