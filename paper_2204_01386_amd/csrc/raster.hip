@@ -1120,7 +1120,9 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX)
     k_fragsort(const int32_t *__restrict__ tri_id, int K, int H, int W, int ntx, int nt, int T,
                int32_t *__restrict__ n_frag, int32_t *__restrict__ n_rec, uint16_t *__restrict__ frag,
                int32_t *__restrict__ rec_tri, int32_t *__restrict__ rec_start,
-               int32_t *__restrict__ tri_counts) {
+               int32_t *__restrict__ tri_counts, int32_t *__restrict__ nlong) {
+    // the long-list queue of k_tt_fill starts empty (read after this launch)
+    if (blockIdx.x == 0 && threadIdx.x == 0) *nlong = 0;
     constexpr KT SENT = (KT)(~(KT)0) << EB;
     constexpr unsigned EMASK = (1u << EB) - 1u;
     constexpr int KMAX = EB == 8 ? 1 : DRESSI_MAX_K;
@@ -1259,8 +1261,13 @@ void dressi_fragindex_view(void *base, int B, int K, int H, int W, int T, FragLi
 // ---------------------------------------------------------------------------
 // triangle -> tiles transpose of the per-tile records
 // ---------------------------------------------------------------------------
+// Lists longer than TT_SHORT entries (a triangle over many tiles) are ordered
+// by a workgroup-wide merge sort instead of per-entry counting (quadratic in
+// the list length); k_tt_fill queues them, at most n / (TT_SHORT + 1).
+#define TT_SHORT 32
 __global__ void k_tt_fill(FragLists fl, int K, int T, int nt, const int32_t *__restrict__ offsets,
-                          int32_t *__restrict__ counts, int2 *__restrict__ entries) {
+                          int32_t *__restrict__ counts, int2 *__restrict__ entries, int32_t *__restrict__ nlong,
+                          int64_t *__restrict__ longk, int cap) {
     // several views: XCD-aware order (each XCD whole views); one view keeps the
     // default interleave, which balances uneven work over the image
     const int bt = (int)gridDim.x > nt ? (int)xcd_block() : (int)blockIdx.x;
@@ -1272,18 +1279,56 @@ __global__ void k_tt_fill(FragLists fl, int K, int T, int nt, const int32_t *__r
         if (t < 0 || t >= T) continue;
         int64_t bt_t = (int64_t)b * T + t;
         // counting back down leaves the counters at zero for the next call
-        int slot = offsets[bt_t] + atomicSub(&counts[bt_t], 1) - 1;
+        const int c = atomicSub(&counts[bt_t], 1);
+        int slot = offsets[bt_t] + c - 1;
         entries[slot] = make_int2(bt, r);
+        // the list's last entry placed queues a long list, once
+        if (c == 1 && offsets[bt_t + 1] - offsets[bt_t] > TT_SHORT) {
+            const int q = atomicAdd(nlong, 1);
+            if (q < cap) longk[q] = bt_t;
+        }
     }
 }
 
-// One thread per entry: its place in its (view, triangle)'s list is the number
-// of that triangle's entries from lower tiles (a triangle has at most one
-// record per tile, so the tile indices in a list are distinct).  Writes the
-// lists in ascending tile order; the work per list grows with the square of
-// its length but runs one thread per entry.
+// Short lists: one thread per entry, whose place in its (view, triangle)'s
+// list is the number of that triangle's entries from lower tiles (a triangle
+// has at most one record per tile, so the tile indices in a list are
+// distinct).  Long lists: one workgroup per queued list, a bottom-up merge
+// sort by tile between the list's stretch of `unsorted` and of `entries`
+// (runs of width 1, 2, 4, ...; an entry's place in its merged pair of runs
+// is its rank in its own run plus the number of smaller tiles in the other,
+// found by binary search).  Either way the lists end in ascending tile order.
 __global__ void k_tt_rank(FragLists fl, int K, int T, int nt, const int32_t *__restrict__ offsets,
-                          const int2 *__restrict__ unsorted, int2 *__restrict__ entries, int64_t nkeys) {
+                          int2 *__restrict__ unsorted, int2 *__restrict__ entries, int64_t nkeys,
+                          const int32_t *__restrict__ nlong, const int64_t *__restrict__ longk, int cap) {
+    const int nq = min(*nlong, cap);
+    for (int q = blockIdx.x; q < nq; q += gridDim.x) {
+        const int64_t key = longk[q];
+        const int lo = offsets[key], n = offsets[key + 1] - lo;
+        int2 *src = unsorted + lo, *dst = entries + lo;
+        for (int w = 1; w < n; w <<= 1) {
+            for (int i = threadIdx.x; i < n; i += blockDim.x) {
+                const int2 x = src[i];
+                const int r = i / w;
+                const int own = r * w, base = (r & ~1) * w;
+                const int ps = (r ^ 1) * w, pe = min(ps + w, n);
+                int a = ps, z = max(ps, pe);
+                while (a < z) {
+                    const int mid = (a + z) >> 1;
+                    if (src[mid].x < x.x) a = mid + 1;
+                    else z = mid;
+                }
+                dst[base + (i - own) + (a - ps)] = x;
+            }
+            __syncthreads();
+            int2 *tswap = src;
+            src = dst;
+            dst = tswap;
+        }
+        if (src != entries + lo)
+            for (int i = threadIdx.x; i < n; i += blockDim.x) entries[lo + i] = src[i];
+        __syncthreads();
+    }
     const int64_t total = offsets[nkeys];   // the number of entries (the scan's total)
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
          e += (int64_t)gridDim.x * blockDim.x) {
@@ -1291,16 +1336,21 @@ __global__ void k_tt_rank(FragLists fl, int K, int T, int nt, const int32_t *__r
         const int t = fl.rec_tri[(int64_t)ent.x * DRESSI_TILE_PIX * K + ent.y];
         const int64_t key = (int64_t)(ent.x / nt) * T + t;
         const int lo = offsets[key], hi = offsets[key + 1];
+        if (hi - lo > TT_SHORT) continue;   // a long list, sorted above
         int rank = 0;
         for (int j = lo; j < hi; j++) rank += unsorted[j].x < ent.x;
         entries[lo + rank] = ent;
     }
 }
 
-// scan temporary, then the unsorted triangle -> tiles entries
+// scan temporary, then the unsorted triangle -> tiles entries, then the
+// long-list queue (its count, then the (view, triangle) keys)
+static size_t tt_long_cap(int64_t ne) { return (size_t)(ne / (TT_SHORT + 1)) + 1; }
+
 size_t dressi_fragindex_tmp_bytes(int B, int K, int H, int W, int T) {
     const int64_t n = (int64_t)B * tiles_x(W) * tiles_y(H) * DRESSI_TILE_PIX * K;
-    return (dressi_scan_tmp_bytes((int64_t)B * T) + 255) / 256 * 256 + sizeof(int2) * (size_t)n;
+    return (dressi_scan_tmp_bytes((int64_t)B * T) + 255) / 256 * 256 + sizeof(int2) * (size_t)n + 8 +
+           sizeof(int64_t) * tt_long_cap(n);
 }
 
 // counts: B*T zero counters (left at zero)
@@ -1310,27 +1360,35 @@ void dressi_build_fragindex(const int32_t *tri_id, int B, int K, int H, int W, i
     TriTiles tt;
     dressi_fragindex_view(base, B, K, H, W, T, fl, tt);
     int ntx = tiles_x(W), nt = ntx * tiles_y(H);
+    const int64_t nb = (int64_t)B * T;
+    int32_t *qcount = reinterpret_cast<int32_t *>(static_cast<char *>(tmp) +
+                                                  (dressi_scan_tmp_bytes(nb) + 255) / 256 * 256 +
+                                                  sizeof(int2) * (size_t)((int64_t)B * nt * DRESSI_TILE_PIX * K));
     if (B * nt > 0) {
         // 32-bit keys while the triangle ids leave room above the local index
         if (K == 1 && T < (1 << 24) - 1)
             DR_LAUNCH("k_fragsort", (k_fragsort<uint32_t, 8>), B * nt, DRESSI_TILE_PIX, 0, s, tri_id, K, H, W, ntx,
-                      nt, T, fl.n_frag, fl.n_rec, fl.frag, fl.rec_tri, fl.rec_start, counts);
+                      nt, T, fl.n_frag, fl.n_rec, fl.frag, fl.rec_tri, fl.rec_start, counts, qcount);
         else if (T < (1 << 21) - 1)
             DR_LAUNCH("k_fragsort", (k_fragsort<uint32_t, 11>), B * nt, DRESSI_TILE_PIX, 0, s, tri_id, K, H, W, ntx,
-                      nt, T, fl.n_frag, fl.n_rec, fl.frag, fl.rec_tri, fl.rec_start, counts);
+                      nt, T, fl.n_frag, fl.n_rec, fl.frag, fl.rec_tri, fl.rec_start, counts, qcount);
         else
             DR_LAUNCH("k_fragsort", (k_fragsort<unsigned long long, 11>), B * nt, DRESSI_TILE_PIX, 0, s, tri_id, K,
-                      H, W, ntx, nt, T, fl.n_frag, fl.n_rec, fl.frag, fl.rec_tri, fl.rec_start, counts);
+                      H, W, ntx, nt, T, fl.n_frag, fl.n_rec, fl.frag, fl.rec_tri, fl.rec_start, counts, qcount);
     }
     int64_t n = (int64_t)B * T;
     dressi_exclusive_scan(counts, tt.offsets, n, tmp, s);
     int2 *unsorted = reinterpret_cast<int2 *>(static_cast<char *>(tmp) +
                                               (dressi_scan_tmp_bytes(n) + 255) / 256 * 256);
     const int64_t ne = (int64_t)B * nt * DRESSI_TILE_PIX * K;   // entry capacity (at least the entries)
+    int32_t *nlong = reinterpret_cast<int32_t *>(unsorted + ne);
+    int64_t *longk = reinterpret_cast<int64_t *>(nlong + 2);
+    const int cap = (int)std::min<size_t>(tt_long_cap(ne), 0x7fffffff);
     if (B * nt > 0) {
-        DR_LAUNCH("k_tt_fill", (k_tt_fill), B * nt, 256, 0, s, fl, K, T, nt, tt.offsets, counts, unsorted);
+        DR_LAUNCH("k_tt_fill", (k_tt_fill), B * nt, 256, 0, s, fl, K, T, nt, tt.offsets, counts, unsorted, nlong,
+                  longk, cap);
         DR_LAUNCH("k_tt_rank", (k_tt_rank), (int)std::min<int64_t>((ne + 255) / 256, 4096), 256, 0, s, fl, K, T,
-                  nt, tt.offsets, unsorted, tt.entries, n);
+                  nt, tt.offsets, unsorted, tt.entries, n, nlong, longk, cap);
     }
 }
 

@@ -605,3 +605,26 @@ def test_adjacency_offsets_are_the_exclusive_scan(B, V):
     corners = a[V + 1:]
     for v in rng.integers(0, V, 8):
         assert np.array_equal(corners[ref[v]:ref[v + 1]], np.nonzero(tris.ravel() == v)[0])
+
+
+@pytest.mark.parametrize("K,r", [(1, 0.0), (2, 0.0), (2, 0.02)])
+def test_raster_bwd_triangles_over_many_tiles(B, K, r):
+    """Triangles spanning hundreds of 16-pixel tiles (their triangle -> tile
+    lists go to the workgroup merge sort, past 32 entries) beside small ones:
+    the rasterization adjoint matches the oracle and two runs give the same
+    bits (every list in tile order)."""
+    H, W = 192, 256
+    big = np.array([[-5, -3], [260, 10], [20, 200], [250, 190], [30, 20], [240, 120]], np.float64)
+    pcb = screen_to_clip(big, H, W, z=np.array([0.3, 0.4, 0.5, 0.6, 0.35, 0.55]),
+                         w=np.array([1.0, 1.3, 0.8, 1.1, 0.9, 1.2]))
+    pcs, ts = random_tiny(21, T=60, H=H, W=W)
+    pc = np.concatenate([pcb, pcs], 0)
+    tris = np.concatenate([np.array([[0, 1, 2], [3, 4, 5]], np.int32), ts + 6]).astype(np.int32)
+    check_raster(B, pc, tris, H, W, K, r, seed=5)
+    tid, bary, dist = B.dressi_rasterize(dev(pc[None]), dev(tris), H, W, K, r, 0)
+    g = torch.randn_like(bary)
+    gd = torch.randn_like(dist) if r > 0 else None
+    a = host(B.dressi_rasterize_bwd(dev(pc[None]), dev(tris), tid, g, gd, r))
+    b_ = host(B.dressi_rasterize_bwd(dev(pc[None]), dev(tris), tid, g, gd, r))
+    assert np.array_equal(a, b_)
+    assert (host(tid)[0, 0] == 0).sum() > 32 * 256, "the first triangle must cover many tiles"
