@@ -443,8 +443,9 @@ int dressi_vertex_attrs(dressi_ctx *ctx, const float *pos, const int32_t *tris, 
 int dressi_vertex_attrs_bwd(dressi_ctx *ctx, const float *pos, const int32_t *tris, int V, int T,
                             int C, const int32_t *adj, const float *grad_out,
                             const float *grad_pos_in, float *grad_pos, void *stream);
-/* dressi_vertex_attrs (vattr [V,C]) and the vertex transform in one launch,
- * the same values: pos_clip [B,V,4] as dressi_transform with B views of mvp
+/* The vertex stage of the render graph (§3.4.1: vertex normals and the
+ * vertex transform): dressi_vertex_attrs (vattr [V,C]) and the vertex
+ * transform in one launch, the same values: pos_clip [B,V,4] as dressi_transform with B views of mvp
  * [B,4,4], or, with vert_view (B = 1), [V,4] as dressi_transform_batched.
  * adj as for dressi_vertex_attrs.  DRESSI_EINVAL for B < 1, or B != 1 with
  * vert_view. */
@@ -574,7 +575,8 @@ int dressi_packed_backward(dressi_ctx *ctx, const dressi_packed_scene *scene, co
                            float *grad_samp, float *grad_bary_uv, int32_t *inv, void *inv_rec, float *grad_tex,
                            void *stream);
 
-/* Geometry adjoints of one image (B = 1, K = 1, hard: after the packed
+/* Geometry adjoints of one image (the reverse pass of §3.4's rasterization,
+ * interpolation and vertex stages; B = 1, K = 1, hard: after the packed
  * pass), in three launches: the same values as dressi_interpolate_bwd of
  * vattr [V, Cv] (Cv = 6 or 9, indexed by tris, grad_out = grad_gbuf
  * [H,W,Cv], grad_bary_in nullable: the texture coordinates' barycentric

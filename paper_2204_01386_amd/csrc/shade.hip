@@ -948,10 +948,13 @@ size_t dr_need_shade(const dressi_limits &l) {
     c.take(dressi_adjacency_tmp_bytes(std::max(l.V, 0), std::max(l.T, 0)));
     c.take(sizeof(float) * 3 * (size_t)std::max(l.V, 0));
     // the loss partials: LOSS_MAX_BLOCKS (dressi_loss_l2) or one per 256
-    // pixels, at most 65536 (dressi_packed_backward)
+    // pixels, at most 65536 (dressi_packed_backward, then the split parts of
+    // its texel gather when it gathers)
     const size_t pix = (size_t)std::max(l.B, 0) * std::max(l.H, 0) * std::max(l.W, 0);
-    return std::max({c.off, sizeof(float) * (size_t)LOSS_MAX_BLOCKS,
-                     sizeof(float) * std::min<size_t>((pix + 255) / 256, 65536)});
+    Carver pb;
+    pb.take(sizeof(float) * std::min<size_t>((pix + 255) / 256, 65536));
+    if (l.tex_cells > 0) pb.take(dressi_invuv_part_bytes(l.tex_cells, 4, std::max(l.B, 1)));
+    return std::max({c.off, sizeof(float) * (size_t)LOSS_MAX_BLOCKS, pb.off});
 }
 
 // ---------------------------------------------------------------------------

@@ -262,3 +262,34 @@ def test_gather_record_entry_point_checks(Bd):
     assert bwd(st._pscene, None, _p(st.g_tex)) == Bd.EINVAL
     assert bwd(st._pscene, _p(st.inv_rec), C.c_void_p(st.g_tex.data_ptr() + 4)) == Bd.EINVAL
     torch.cuda.synchronize()
+
+
+def test_geometry_bwd_entry_point_checks(Bd):
+    """dressi_geometry_bwd refuses, before any launch, an attribute width
+    other than 6 or 9, a culling flag other than 0 or 1, a view set without
+    its per-vertex matrices, and null buffers; the step's own call succeeds."""
+    from paper_2204_01386_amd.pipeline import Step, _p
+    s = scenes.config2(H=32, subdiv=2, tex_size=16)
+    st = Step(s)
+    assert st.packed_geo
+    st.run()
+    torch.cuda.synchronize()
+    lib, h = Bd._lib, st.ctx.handle
+
+    def call(Cv=st.Cv, cull=0, tri_view=None, views=None, vert_view=None, pos=st.pos, g_pos=st.g_pos):
+        return lib.dressi_geometry_bwd(h, _p(pos), _p(st.vattr), st.V, Cv, _p(st.tris), st.T, _p(st.pos_clip),
+                                       _p(st.mvp), _p(vert_view), _p(tri_view), _p(views), 1, st.H, st.W, cull,
+                                       _p(st.tri_id), _p(st.bary), _p(st.g_gbuf), _p(st.g_bary_uv),
+                                       _p(st.frag_index), _p(st.adj), _p(st.g_vattr), _p(st.g_bary),
+                                       _p(st.g_clip), _p(g_pos), Bd._stream())
+
+    assert call() == 0
+    assert call(Cv=7) == Bd.EINVAL
+    assert call(cull=2) == Bd.EINVAL
+    views = torch.tensor([[0, 0, st.W, st.H]], dtype=torch.int32, device="cuda")
+    tv = torch.zeros(st.T, dtype=torch.int32, device="cuda")
+    assert call(tri_view=tv, views=views) == Bd.EINVAL          # no per-vertex matrices
+    assert call(tri_view=tv) == Bd.EINVAL                       # views missing
+    assert call(pos=None) == Bd.EINVAL
+    assert call(g_pos=None) == Bd.EINVAL
+    torch.cuda.synchronize()
