@@ -1294,18 +1294,23 @@ __global__ void k_tt_fill(FragLists fl, int K, int T, int nt, const int32_t *__r
 // list is the number of that triangle's entries from lower tiles (a triangle
 // has at most one record per tile, so the tile indices in a list are
 // distinct).  Long lists: one workgroup per queued list, a bottom-up merge
-// sort by tile between the list's stretch of `unsorted` and of `entries`
-// (runs of width 1, 2, 4, ...; an entry's place in its merged pair of runs
-// is its rank in its own run plus the number of smaller tiles in the other,
-// found by binary search).  Either way the lists end in ascending tile order.
+// sort by tile from the list's stretch of `unsorted`, ping-ponging between
+// its stretches of `sbuf` and `entries` (runs of width 1, 2, 4, ...; an
+// entry's place in its merged pair of runs is its rank in its own run plus
+// the number of smaller tiles in the other, found by binary search).
+// `unsorted` is only read, so the short lists' threads never see a list
+// being sorted.  Either way the lists end in ascending tile order.
 __global__ void k_tt_rank(FragLists fl, int K, int T, int nt, const int32_t *__restrict__ offsets,
-                          int2 *__restrict__ unsorted, int2 *__restrict__ entries, int64_t nkeys,
-                          const int32_t *__restrict__ nlong, const int64_t *__restrict__ longk, int cap) {
+                          const int2 *__restrict__ unsorted, int2 *__restrict__ entries, int2 *__restrict__ sbuf,
+                          int64_t nkeys, const int32_t *__restrict__ nlong, const int64_t *__restrict__ longk,
+                          int cap) {
     const int nq = min(*nlong, cap);
     for (int q = blockIdx.x; q < nq; q += gridDim.x) {
         const int64_t key = longk[q];
         const int lo = offsets[key], n = offsets[key + 1] - lo;
-        int2 *src = unsorted + lo, *dst = entries + lo;
+        for (int i = threadIdx.x; i < n; i += blockDim.x) sbuf[lo + i] = unsorted[lo + i];
+        __syncthreads();
+        int2 *src = sbuf + lo, *dst = entries + lo;
         for (int w = 1; w < n; w <<= 1) {
             for (int i = threadIdx.x; i < n; i += blockDim.x) {
                 const int2 x = src[i];
@@ -1344,13 +1349,14 @@ __global__ void k_tt_rank(FragLists fl, int K, int T, int nt, const int32_t *__r
 }
 
 // scan temporary, then the unsorted triangle -> tiles entries, then the
-// long-list queue (its count, then the (view, triangle) keys)
+// long-list queue (its count, then the (view, triangle) keys), then the
+// long lists' sort buffer
 static size_t tt_long_cap(int64_t ne) { return (size_t)(ne / (TT_SHORT + 1)) + 1; }
 
 size_t dressi_fragindex_tmp_bytes(int B, int K, int H, int W, int T) {
     const int64_t n = (int64_t)B * tiles_x(W) * tiles_y(H) * DRESSI_TILE_PIX * K;
     return (dressi_scan_tmp_bytes((int64_t)B * T) + 255) / 256 * 256 + sizeof(int2) * (size_t)n + 8 +
-           sizeof(int64_t) * tt_long_cap(n);
+           sizeof(int64_t) * tt_long_cap(n) + sizeof(int2) * (size_t)n;
 }
 
 // counts: B*T zero counters (left at zero)
@@ -1383,12 +1389,13 @@ void dressi_build_fragindex(const int32_t *tri_id, int B, int K, int H, int W, i
     const int64_t ne = (int64_t)B * nt * DRESSI_TILE_PIX * K;   // entry capacity (at least the entries)
     int32_t *nlong = reinterpret_cast<int32_t *>(unsorted + ne);
     int64_t *longk = reinterpret_cast<int64_t *>(nlong + 2);
+    int2 *sbuf = reinterpret_cast<int2 *>(longk + tt_long_cap(ne));
     const int cap = (int)std::min<size_t>(tt_long_cap(ne), 0x7fffffff);
     if (B * nt > 0) {
         DR_LAUNCH("k_tt_fill", (k_tt_fill), B * nt, 256, 0, s, fl, K, T, nt, tt.offsets, counts, unsorted, nlong,
                   longk, cap);
         DR_LAUNCH("k_tt_rank", (k_tt_rank), (int)std::min<int64_t>((ne + 255) / 256, 4096), 256, 0, s, fl, K, T,
-                  nt, tt.offsets, unsorted, tt.entries, n, nlong, longk, cap);
+                  nt, tt.offsets, unsorted, tt.entries, sbuf, n, nlong, longk, cap);
     }
 }
 
