@@ -265,6 +265,18 @@ int dressi_adjacency(dressi_ctx *ctx, const int32_t *tris, int T, int V, int32_t
 size_t dressi_fragment_index_bytes(int B, int K, int H, int W, int T);
 int dressi_fragment_index(dressi_ctx *ctx, const int32_t *tri_id, int B, int K, int H, int W, int T,
                           void *index, void *stream);
+/* Rasterization (Algorithm 2 for one hard layer) and the fragment index of
+ * its result in one call: the outputs of dressi_rasterize with K = 1, r = 0
+ * (tri_id [B,H,W], bary [B,H,W,2]) and of dressi_fragment_index of that
+ * tri_id (index: dressi_fragment_index_bytes(B, 1, H, W, T) bytes).  With the
+ * binless strategy (DRESSI_TUNE_HARD_RASTER = 3) each tile's resolve hands
+ * its triangle ids to the tile's fragment sort in the same launch; with the
+ * others the two calls run in sequence.  The caller owns every buffer; the
+ * library's scratch and zero-kept counters serve the launches.  Errors:
+ * DRESSI_EINVAL for a null pointer, B, V or T negative, T >= 2^31 - 1, or H
+ * or W outside 1..32767, with nothing launched. */
+int dressi_rasterize_indexed(dressi_ctx *ctx, const float *pos_clip, const int32_t *tris, int B, int V, int T,
+                             int H, int W, int cull, int32_t *tri_id, float *bary, void *index, void *stream);
 
 /* ----------------------------------------------------------------------------
  * Attribute interpolation (BuildInterpolate, appendix listing):

@@ -1114,29 +1114,20 @@ __device__ __forceinline__ int run_rank(const KT *run, KT v) {
 // One workgroup per tile: the tile's K*256 keys are sorted in runs of 64 (one
 // wavefront each, in registers), every key is placed at its rank (its index in
 // its run plus its rank in each other run), and the sorted list is cut into
-// per-triangle records.
+// per-triangle records.  tv: this lane's pixel's triangle id in each layer
+// (-1: none); the whole workgroup calls it.
 template <typename KT, int EB>
-__global__ void __launch_bounds__(DRESSI_TILE_PIX)
-    k_fragsort(const int32_t *__restrict__ tri_id, int K, int H, int W, int ntx, int nt, int T,
-               int32_t *__restrict__ n_frag, int32_t *__restrict__ n_rec, uint16_t *__restrict__ frag,
-               int32_t *__restrict__ rec_tri, int32_t *__restrict__ rec_start,
-               int32_t *__restrict__ tri_counts, int32_t *__restrict__ nlong) {
-    // the long-list queue of k_tt_fill starts empty (read after this launch)
-    if (blockIdx.x == 0 && threadIdx.x == 0) *nlong = 0;
+__device__ __forceinline__ void fragsort_tile(int bt, int b, const int *tv, int K, int T,
+                                              int32_t *__restrict__ n_frag, int32_t *__restrict__ n_rec,
+                                              uint16_t *__restrict__ frag, int32_t *__restrict__ rec_tri,
+                                              int32_t *__restrict__ rec_start, int32_t *__restrict__ tri_counts) {
     constexpr KT SENT = (KT)(~(KT)0) << EB;
     constexpr unsigned EMASK = (1u << EB) - 1u;
     constexpr int KMAX = EB == 8 ? 1 : DRESSI_MAX_K;
     __shared__ KT runs[KMAX * DRESSI_TILE_PIX];
     __shared__ KT keys[KMAX * DRESSI_TILE_PIX];
     __shared__ int wsum[DRESSI_TILE_PIX / 64];
-    // several views: XCD-aware order (each XCD whole views); one view keeps the
-    // default interleave, which balances uneven work over the image
-    const int bt = (int)gridDim.x > nt ? (int)xcd_block() : (int)blockIdx.x;
-    const int b = bt / nt, tile = bt - b * nt;
-    const int tx = tile % ntx, ty = tile / ntx;
     const int p = threadIdx.x;
-    const int x = tx * DRESSI_TILE + (p & (DRESSI_TILE - 1));
-    const int y = ty * DRESSI_TILE + p / DRESSI_TILE;
     const int np = K * DRESSI_TILE_PIX, nruns = np / 64;
     int any = 0;
     KT kv[KMAX];
@@ -1144,12 +1135,10 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX)
     for (int k = 0; k < KMAX; k++) {
         const int e = k * DRESSI_TILE_PIX + p;
         kv[k] = SENT | (KT)e;
-        if (k < K && x < W && y < H) {
-            const int t = tri_id[(((int64_t)b * K + k) * H + y) * W + x];
-            if (t >= 0) {
-                kv[k] = ((KT)(t < T ? t : T) << EB) | (KT)e;
-                any = 1;
-            }
+        const int t = k < K ? tv[k] : -1;
+        if (t >= 0) {
+            kv[k] = ((KT)(t < T ? t : T) << EB) | (KT)e;
+            any = 1;
         }
     }
     if (!__syncthreads_or(any)) {
@@ -1224,6 +1213,68 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX)
         n_frag[bt] = np;
     }
     if (p == 0) n_rec[bt] = total_heads;
+}
+
+template <typename KT, int EB>
+__global__ void __launch_bounds__(DRESSI_TILE_PIX)
+    k_fragsort(const int32_t *__restrict__ tri_id, int K, int H, int W, int ntx, int nt, int T,
+               int32_t *__restrict__ n_frag, int32_t *__restrict__ n_rec, uint16_t *__restrict__ frag,
+               int32_t *__restrict__ rec_tri, int32_t *__restrict__ rec_start,
+               int32_t *__restrict__ tri_counts, int32_t *__restrict__ nlong) {
+    // the long-list queue of k_tt_fill starts empty (read after this launch)
+    if (blockIdx.x == 0 && threadIdx.x == 0) *nlong = 0;
+    constexpr int KMAX = EB == 8 ? 1 : DRESSI_MAX_K;
+    // several views: XCD-aware order (each XCD whole views); one view keeps the
+    // default interleave, which balances uneven work over the image
+    const int bt = (int)gridDim.x > nt ? (int)xcd_block() : (int)blockIdx.x;
+    const int b = bt / nt, tile = bt - b * nt;
+    const int tx = tile % ntx, ty = tile / ntx;
+    const int p = threadIdx.x;
+    const int x = tx * DRESSI_TILE + (p & (DRESSI_TILE - 1));
+    const int y = ty * DRESSI_TILE + p / DRESSI_TILE;
+    int tv[KMAX];
+#pragma unroll
+    for (int k = 0; k < KMAX; k++)
+        tv[k] = (k < K && x < W && y < H) ? tri_id[(((int64_t)b * K + k) * H + y) * W + x] : -1;
+    fragsort_tile<KT, EB>(bt, b, tv, K, T, n_frag, n_rec, frag, rec_tri, rec_start, tri_counts);
+}
+
+// The binless resolve of one tile (K = 1, as k_raster_direct_resolve)
+// followed by the tile's fragment sort (as k_fragsort): the pixels' triangle
+// ids go to the sort in registers.
+template <typename KT, int EB>
+__global__ void __launch_bounds__(DRESSI_TILE_PIX)
+    k_raster_direct_resolve_sort(const float4 *__restrict__ pos_clip, const int32_t *__restrict__ tris,
+                                 Viewports vp, int B, int V, int T, int H, int W, int cull, int ntx, int nt,
+                                 unsigned long long *__restrict__ zbuf, int32_t *__restrict__ tri_id,
+                                 float2 *__restrict__ bary, FragLists fl, int32_t *__restrict__ tri_counts,
+                                 int32_t *__restrict__ nlong) {
+    // the long-list queue of k_tt_fill starts empty (read after this launch)
+    if (blockIdx.x == 0 && threadIdx.x == 0) *nlong = 0;
+    const int bt = (int)gridDim.x > nt ? (int)xcd_block() : (int)blockIdx.x;
+    const int b = bt / nt, tile = bt - b * nt;
+    const int tx = tile % ntx, ty = tile / ntx;
+    const int p = threadIdx.x;
+    const int x = tx * DRESSI_TILE + (p & (DRESSI_TILE - 1));
+    const int y = ty * DRESSI_TILE + p / DRESSI_TILE;
+    int t = -1;
+    if (x < W && y < H) {
+        const int64_t i = ((int64_t)b * H + y) * W + x;
+        const unsigned long long c = zbuf[i];
+        if (c == 0ull) {   // no fragment
+            tri_id[i] = -1;
+            bary[i] = make_float2(0.0f, 0.0f);
+        } else {
+            zbuf[i] = 0ull;
+            const unsigned long long v = ~c;
+            t = (int)(v & 0xffffffffu);
+            TriSetup s;
+            direct_setup(pos_clip, tris, vp, b, V, t, H, W, cull, s);   // valid: it produced the key
+            resolve_frag<false>(s, t, DRESSI_SUBPIX * x + DRESSI_SUBPIX / 2, DRESSI_SUBPIX * y + DRESSI_SUBPIX / 2,
+                                __uint_as_float((unsigned)(v >> 32)), 0.0f, i, tri_id, bary, nullptr);
+        }
+    }
+    fragsort_tile<KT, EB>(bt, b, &t, 1, T, fl.n_frag, fl.n_rec, fl.frag, fl.rec_tri, fl.rec_start, tri_counts);
 }
 
 static void fragindex_layout(int B, int K, int H, int W, int T, Carver &c, size_t *o) {
@@ -1359,6 +1410,17 @@ size_t dressi_fragindex_tmp_bytes(int B, int K, int H, int W, int T) {
            sizeof(int64_t) * tt_long_cap(n) + sizeof(int2) * (size_t)n;
 }
 
+static void fragindex_lists(int B, int K, int H, int W, int T, const FragLists &fl, const TriTiles &tt, void *tmp,
+                            int32_t *counts, hipStream_t s);
+
+// the long-list queue's count in a fragment index's temporary
+static int32_t *fragindex_qcount(void *tmp, int B, int K, int H, int W, int T) {
+    const int64_t nb = (int64_t)B * T;
+    const int64_t ne = (int64_t)B * tiles_x(W) * tiles_y(H) * DRESSI_TILE_PIX * K;
+    return reinterpret_cast<int32_t *>(static_cast<char *>(tmp) + (dressi_scan_tmp_bytes(nb) + 255) / 256 * 256 +
+                                       sizeof(int2) * (size_t)ne);
+}
+
 // counts: B*T zero counters (left at zero)
 void dressi_build_fragindex(const int32_t *tri_id, int B, int K, int H, int W, int T, void *base,
                             void *tmp, int32_t *counts, hipStream_t s) {
@@ -1366,10 +1428,7 @@ void dressi_build_fragindex(const int32_t *tri_id, int B, int K, int H, int W, i
     TriTiles tt;
     dressi_fragindex_view(base, B, K, H, W, T, fl, tt);
     int ntx = tiles_x(W), nt = ntx * tiles_y(H);
-    const int64_t nb = (int64_t)B * T;
-    int32_t *qcount = reinterpret_cast<int32_t *>(static_cast<char *>(tmp) +
-                                                  (dressi_scan_tmp_bytes(nb) + 255) / 256 * 256 +
-                                                  sizeof(int2) * (size_t)((int64_t)B * nt * DRESSI_TILE_PIX * K));
+    int32_t *qcount = fragindex_qcount(tmp, B, K, H, W, T);
     if (B * nt > 0) {
         // 32-bit keys while the triangle ids leave room above the local index
         if (K == 1 && T < (1 << 24) - 1)
@@ -1382,6 +1441,15 @@ void dressi_build_fragindex(const int32_t *tri_id, int B, int K, int H, int W, i
             DR_LAUNCH("k_fragsort", (k_fragsort<unsigned long long, 11>), B * nt, DRESSI_TILE_PIX, 0, s, tri_id, K,
                       H, W, ntx, nt, T, fl.n_frag, fl.n_rec, fl.frag, fl.rec_tri, fl.rec_start, counts, qcount);
     }
+    fragindex_lists(B, K, H, W, T, fl, tt, tmp, counts, s);
+}
+
+// The triangle -> tile lists of a fragment index whose tiles are sorted
+// (counts: the per-(view, triangle) record counts the sort left, set back to
+// zero here).
+static void fragindex_lists(int B, int K, int H, int W, int T, const FragLists &fl, const TriTiles &tt, void *tmp,
+                            int32_t *counts, hipStream_t s) {
+    const int nt = tiles_x(W) * tiles_y(H);
     int64_t n = (int64_t)B * T;
     dressi_exclusive_scan(counts, tt.offsets, n, tmp, s);
     int2 *unsorted = reinterpret_cast<int2 *>(static_cast<char *>(tmp) +
@@ -1418,6 +1486,55 @@ extern "C" int dressi_fragment_index(dressi_ctx *ctx, const int32_t *tri_id, int
     if (rc) return rc;
     dressi_build_fragindex(tri_id, B, K, H, W, T, index, ctx->scratch, ctx->counters, st);
     return dressi_launch_check(ctx, "fragment_index");
+}
+
+extern "C" int dressi_rasterize_indexed(dressi_ctx *ctx, const float *pos_clip, const int32_t *tris, int B, int V,
+                                        int T, int H, int W, int cull, int32_t *tri_id, float *bary,
+                                        void *index, void *stream) {
+    int rc = check_raster_args(ctx, pos_clip, tris, B, V, T, H, W, 1, 0.0f);
+    if (rc) return rc;
+    if (!tri_id || !bary || !index)
+        return dressi_fail(ctx, DRESSI_EINVAL, "rasterize_indexed: null tri_id, bary or index");
+    if (B == 0) return DRESSI_OK;
+    hipStream_t st = (hipStream_t)stream;
+    if (ctx->hard_raster != 3) {
+        // a binned strategy: the two calls in sequence
+        rc = rasterize_impl(ctx, pos_clip, tris, Viewports{nullptr, nullptr}, B, V, T, H, W, 1, 0.0f, cull, tri_id,
+                            bary, nullptr, stream);
+        if (rc) return rc;
+        return dressi_fragment_index(ctx, tri_id, B, 1, H, W, T, index, stream);
+    }
+    // without bins: the per-pixel keys after the record counters, both kept at zero
+    const size_t nc = ((size_t)B * T + 1) / 2 * 2;
+    const int64_t npx = (int64_t)B * H * W;
+    rc = dressi_scratch(ctx, dressi_fragindex_tmp_bytes(B, 1, H, W, T), st);
+    if (rc) return rc;
+    rc = dressi_counters(ctx, nc + 2 * (size_t)npx, st);
+    if (rc) return rc;
+    int32_t *counts = ctx->counters;
+    unsigned long long *zbuf = reinterpret_cast<unsigned long long *>(ctx->counters + nc);
+    const float4 *pc4 = reinterpret_cast<const float4 *>(pos_clip);
+    const Viewports vp{nullptr, nullptr};
+    const int64_t ntri = (int64_t)B * T;
+    if (ntri > 0)
+        DR_LAUNCH("k_raster_direct", (k_raster_direct), (int)((ntri + 255) / 256), 256, 0, st, pc4, tris, vp, B, V,
+                  T, H, W, cull, zbuf);
+    FragLists fl;
+    TriTiles tt;
+    dressi_fragindex_view(index, B, 1, H, W, T, fl, tt);
+    const int ntx = tiles_x(W), nt = ntx * tiles_y(H);
+    void *tmp = ctx->scratch;
+    int32_t *qcount = fragindex_qcount(tmp, B, 1, H, W, T);
+    float2 *b2 = reinterpret_cast<float2 *>(bary);
+    if (T < (1 << 24) - 1)
+        DR_LAUNCH("k_raster_direct_resolve_sort", (k_raster_direct_resolve_sort<uint32_t, 8>), B * nt, DRESSI_TILE_PIX, 0,
+                  st, pc4, tris, vp, B, V, T, H, W, cull, ntx, nt, zbuf, tri_id, b2, fl, counts, qcount);
+    else
+        DR_LAUNCH("k_raster_direct_resolve_sort", (k_raster_direct_resolve_sort<unsigned long long, 11>), B * nt,
+                  DRESSI_TILE_PIX, 0, st, pc4, tris, vp, B, V, T, H, W, cull, ntx, nt, zbuf, tri_id, b2, fl, counts,
+                  qcount);
+    fragindex_lists(B, 1, H, W, T, fl, tt, tmp, counts, st);
+    return dressi_launch_check(ctx, "rasterize_indexed");
 }
 
 // binary search of triangle t among the sorted records of one tile; returns
@@ -1956,8 +2073,11 @@ extern "C" int dressi_reserve_limits(dressi_ctx *ctx, const dressi_limits *l) {
     if (rc) return rc;
     const size_t nt = (size_t)tiles_x(l->W) * tiles_y(l->H);
     size_t nc = std::max((size_t)std::max(l->B, 1) * nt, (size_t)std::max(l->B, 1) * std::max(l->T, 0));
-    // one layer: the binless hard rasterizer's per-pixel keys (two counters a pixel)
-    if (l->K <= 1) nc = std::max(nc, 2 * (size_t)std::max(l->B, 1) * std::max(l->H, 0) * std::max(l->W, 0));
+    // one layer: the binless hard rasterizer's per-pixel keys (two counters a
+    // pixel; after the record counters when it builds the fragment index too)
+    if (l->K <= 1)
+        nc = std::max(nc, ((size_t)std::max(l->B, 1) * std::max(l->T, 0) + 1) / 2 * 2 +
+                              2 * (size_t)std::max(l->B, 1) * std::max(l->H, 0) * std::max(l->W, 0));
     return dressi_counters(ctx, nc, nullptr);
 }
 

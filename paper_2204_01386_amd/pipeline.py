@@ -304,11 +304,15 @@ class Step(_TwoStreams):
         self.packed_geo = self.packed and B == 1
         self.hard_raster = None     # rasterization strategy chosen by autotune() (None: triangle-parallel)
         self.hybrid_weight = HYBRID_WEIGHT_DEFAULT
+        # one hard layer: the fragment index built in the rasterization's call
+        self.fuse_index = True
         self._calibrate_bins()
 
-    def _raster(self, attrs=False):
+    def _raster(self, attrs=False, index=False):
         """Transform and rasterization; with `attrs`, the vertex attributes
-        in the transform's launch (dressi_vertex_stage)."""
+        in the transform's launch (dressi_vertex_stage); with `index` (one
+        hard layer), the fragment index in the rasterization's call
+        (dressi_rasterize_indexed)."""
         h, st = self.ctx.handle, self._s()
         self.ctx.tune(Bd.TUNE_HARD_RASTER, self.hard_raster or 0)
         self.ctx.tune(Bd.TUNE_HYBRID_WEIGHT, self.hybrid_weight)
@@ -324,6 +328,10 @@ class Step(_TwoStreams):
                                                    self.H, self.W, self.K, self.r, 0, self.delta, self.blend,
                                                    _p(self.tri_id), _p(self.bary), _p(self.dist), st),
                       "rasterize_banded")
+        elif index:
+            self._chk(_lib.dressi_rasterize_indexed(h, _p(self.pos_clip), _p(self.tris), self.B, self.V, self.T,
+                                                    self.H, self.W, 0, _p(self.tri_id), _p(self.bary),
+                                                    _p(self.frag_index), st), "rasterize_indexed")
         else:
             self._chk(_lib.dressi_rasterize(h, _p(self.pos_clip), _p(self.tris), self.B, self.V, self.T, self.H,
                                             self.W, self.K, self.r, 0, _p(self.tri_id), _p(self.bary),
@@ -386,11 +394,23 @@ class Step(_TwoStreams):
             self._raster()
             self._join()
         else:
-            self._raster(attrs=True)
+            # one hard layer: the fragment index in the rasterization's call
+            fused = self.fuse_index and K == 1 and self.r == 0 and not self.band and not self._on("index")
+            self._raster(attrs=True, index=fused)
+            if fused:
+                self._after_index()
+                return
         # the backward's fragment index beside the rest of the forward
         self._fork("index")
         self._chk2(_lib.dressi_fragment_index(self._h2("index"), _p(self.tri_id), B, K, H, W, T, _p(self.frag_index),
                                               self._sa("index")), "fragment_index", "index")
+        self._after_index()
+
+    def _after_index(self):
+        """The forward's per-fragment stages, after the rasterization."""
+        h, s = self.ctx.handle, self._s()
+        B, V, T, H, W, K = self.B, self.V, self.T, self.H, self.W, self.K
+        ck = self._chk
         if self.packed:
             ck(_lib.dressi_packed_forward(h, C.byref(self._pscene), _p(self.tri_id), _p(self.bary), B, H, W,
                                           _p(self.gbuf), _p(self.uvbuf), _p(self.samp), _p(self.color),

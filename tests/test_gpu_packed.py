@@ -293,3 +293,77 @@ def test_geometry_bwd_entry_point_checks(Bd):
     assert call(pos=None) == Bd.EINVAL
     assert call(g_pos=None) == Bd.EINVAL
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("views", [1, 2])
+def test_rasterize_indexed_matches_two_calls(Bd, views):
+    """dressi_rasterize_indexed gives the triangle ids and barycentrics of
+    dressi_rasterize and a fragment index that the adjoints read exactly as
+    dressi_fragment_index's (the same gradients, bitwise), with the binless
+    strategy (resolve and sort in one launch) and a binned one; the step
+    gives the same bits with the index fused or built on its own."""
+    import ctypes as C
+    from paper_2204_01386_amd.pipeline import Step, make_target
+    s = _ragged_two_views(9) if views == 2 else scenes.config2(H=96, subdiv=4, tex_size=64)
+    st = Step(s, target=make_target(s))
+    lib, ctx = Bd._lib, st.ctx
+    B, H, W, T, V = st.B, st.H, st.W, st.T, st.V
+    nbytes = int(lib.dressi_fragment_index_bytes(B, 1, H, W, T))
+    g = torch.randn((B, 1, H, W, 2), device="cuda")
+    outs = []
+    for hr, fused in ((3, True), (0, True), (3, False)):
+        ctx.tune(Bd.TUNE_HARD_RASTER, hr)
+        tid = torch.empty((B, 1, H, W), dtype=torch.int32, device="cuda")
+        bary = torch.empty((B, 1, H, W, 2), device="cuda")
+        fi = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        p = lambda t: C.c_void_p(t.data_ptr())
+        if fused:
+            assert lib.dressi_rasterize_indexed(ctx.handle, p(st.pos_clip), p(st.tris), B, V, T, H, W, 0, p(tid),
+                                                p(bary), p(fi), Bd._stream()) == 0
+        else:
+            assert lib.dressi_rasterize(ctx.handle, p(st.pos_clip), p(st.tris), B, V, T, H, W, 1, 0.0, 0, p(tid),
+                                        p(bary), None, Bd._stream()) == 0
+            assert lib.dressi_fragment_index(ctx.handle, p(tid), B, 1, H, W, T, p(fi), Bd._stream()) == 0
+        gp = Bd.dressi_rasterize_bwd(st.pos_clip, st.tris, tid, g, frag_index=fi, adj=st.adj)
+        torch.cuda.synchronize()
+        outs.append((host(tid).copy(), host(bary).copy(), host(gp).copy()))
+    ctx.tune(Bd.TUNE_HARD_RASTER, 0)
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            assert np.array_equal(a, b)
+    assert (outs[0][0] >= 0).any()
+    # the whole step: fused index against the index built on the second stream
+    res = {}
+    for conc in (False, "index"):
+        st2 = Step(s, target=make_target(s))
+        st2.hard_raster = 3
+        st2.concurrent = conc
+        st2.run()
+        torch.cuda.synchronize()
+        res[conc] = {k: host(v).copy() for k, v in st2.grads().items()}
+    for k in res[False]:
+        assert np.array_equal(res[False][k], res["index"][k]), k
+
+
+def test_rasterize_indexed_argument_checks(Bd):
+    """EINVAL, with nothing written, for a null output or a bad size."""
+    import ctypes as C
+    from paper_2204_01386_amd.pipeline import Step, make_target
+    s = scenes.config2(H=32, subdiv=2, tex_size=32)
+    st = Step(s, target=make_target(s))
+    lib, ctx = Bd._lib, st.ctx
+    B, H, W, T, V = st.B, st.H, st.W, st.T, st.V
+    p = lambda t: C.c_void_p(t.data_ptr())
+    tid = torch.full((B, 1, H, W), 7, dtype=torch.int32, device="cuda")
+    bary = torch.empty((B, 1, H, W, 2), device="cuda")
+    fi = torch.empty(int(lib.dressi_fragment_index_bytes(B, 1, H, W, T)), dtype=torch.uint8, device="cuda")
+    args = [ctx.handle, p(st.pos_clip), p(st.tris), B, V, T, H, W, 0, p(tid), p(bary), p(fi), Bd._stream()]
+    for i, bad in ((9, None), (10, None), (11, None), (3, -1), (5, -1), (6, 0), (7, 40000), (1, None)):
+        a = list(args)
+        a[i] = bad
+        assert lib.dressi_rasterize_indexed(*a) == Bd.EINVAL, (i, bad)
+    torch.cuda.synchronize()
+    assert bool((tid == 7).all())
+    assert lib.dressi_rasterize_indexed(*args) == 0
+    torch.cuda.synchronize()
+    assert not bool((tid == 7).all())
