@@ -293,15 +293,22 @@ __device__ __forceinline__ TriSetup dr_setup(const float4 *pc, int v0, int v1, i
     float4 p[3];
     int X[3], Y[3];
     float hw = 0.5f * (float)W, hh = 0.5f * (float)H;
+    // The three vertices' tests are combined into one branch, so that their
+    // loads are in flight together rather than one after another's test (the
+    // indices are valid: every caller checks them).
+#pragma unroll
+    for (int i = 0; i < 3; i++) p[i] = pc[vid[i]];
+    bool ok = true;
 #pragma unroll
     for (int i = 0; i < 3; i++) {
-        p[i] = pc[vid[i]];
-        if (!(p[i].w > 0.0f)) return s;
-        if (!dr_snap(p[i].x, p[i].w, hw, false, X[i])) return s;
-        if (!dr_snap(p[i].y, p[i].w, hh, true, Y[i])) return s;
+        X[i] = Y[i] = 0;
+        ok = ok & (p[i].w > 0.0f);
+        ok = ok & dr_snap(p[i].x, p[i].w, hw, false, X[i]);
+        ok = ok & dr_snap(p[i].y, p[i].w, hh, true, Y[i]);
         X[i] += DRESSI_SUBPIX * ox;
         Y[i] += DRESSI_SUBPIX * oy;
     }
+    if (!ok) return s;
     int64_t A2 = (int64_t)(X[1] - X[0]) * (int64_t)(Y[2] - Y[0]) -
                  (int64_t)(X[2] - X[0]) * (int64_t)(Y[1] - Y[0]);
     if (A2 == 0) return s;
@@ -356,6 +363,21 @@ __device__ __forceinline__ TriSetup dr_setup(const float4 *pc, int v0, int v1, i
     s.box1 = y0 | (y1 << 16);
     s.meta |= 1;
     return s;
+}
+
+// dr_setup of triangle `tv` (three vertex indices), empty when an index is
+// outside [0, V)
+__device__ __forceinline__ TriSetup dr_setup_tri(const float4 *pc, const int32_t *tv, int V, int H, int W, int ox,
+                                                 int oy, int cull, int margin) {
+    const int v0 = tv[0], v1 = tv[1], v2 = tv[2];
+    if ((unsigned)v0 >= (unsigned)V || (unsigned)v1 >= (unsigned)V || (unsigned)v2 >= (unsigned)V) {
+        TriSetup s;
+        s.meta = 0;
+        s.box0 = s.box1 = 1;
+        s.hbox0 = s.hbox1 = 1;
+        return s;
+    }
+    return dr_setup(pc, v0, v1, v2, H, W, ox, oy, cull, margin);
 }
 
 __device__ __forceinline__ int dr_corner(int meta, int i) { return (meta >> (4 + 2 * i)) & 3; }

@@ -1700,7 +1700,7 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX)
             if (t < 0 || t >= T) continue;
             const int32_t *tv = tris + 3 * (int64_t)t;
             const int4 q = dr_viewport(vp, t, H, W);
-            TriSetup s = dr_setup(pc, tv[0], tv[1], tv[2], q.w, q.z, q.x, q.y, cull, margin);
+            TriSetup s = dr_setup_tri(pc, tv, V, q.w, q.z, q.x, q.y, cull, margin);
             float *dst = vals + (k * DRESSI_TILE_PIX + p) * 9;
             if (!(s.meta & 1)) {
 #pragma unroll
@@ -1916,7 +1916,7 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX) __attribute__((amdgpu_waves_p
         if (t >= 0 && t < T) {
             const int32_t *tv = tris + 3 * (int64_t)t;
             const int4 q = dr_viewport(vp, t, H, W);
-            TriSetup s = dr_setup(pos_clip, tv[0], tv[1], tv[2], q.w, q.z, q.x, q.y, cull, 0);
+            TriSetup s = dr_setup_tri(pos_clip, tv, Va, q.w, q.z, q.x, q.y, cull, 0);
             float *dst = rvals + p * 9;
             if (!(s.meta & 1)) {
 #pragma unroll

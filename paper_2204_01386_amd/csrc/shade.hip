@@ -1000,8 +1000,8 @@ __global__ void __launch_bounds__(256)
     }
     if (i >= n) return;
     const int t = tri_id[i];
-    edge[i] = 0;
     if (t < 0) {
+        edge[i] = 0;
         color[3 * i] = 0.0f; color[3 * i + 1] = 0.0f; color[3 * i + 2] = 0.0f;
         sil[i] = 0.0f;
         if (skip_empty) return;
@@ -1013,43 +1013,87 @@ __global__ void __launch_bounds__(256)
         }
         return;
     }
+    // Every load is issued before the first store (the outputs may alias the
+    // inputs as far as the compiler knows, so a store would hold back each
+    // later load): the corners, the barycentrics, the camera and the texture
+    // layer together, then the attribute and coordinate rows, then the taps.
     const float2 w = bary[i];
+    const bool view = mode != DRESSI_SHADE_LAMBERT;
+    int v0 = -1, v1 = -1, v2 = -1, u0 = -1, u1 = -1, u2 = -1, layer = 0;
+    float eye[3] = {0.0f, 0.0f, 0.0f};
+    if (t < sc.T) {
+        const int32_t *tv = sc.tris + 3 * (int64_t)t;
+        v0 = tv[0]; v1 = tv[1]; v2 = tv[2];
+        if (TEX) {
+            const int32_t *uv = sc.uv_tris + 3 * (int64_t)t;
+            u0 = uv[0]; u1 = uv[1]; u2 = uv[2];
+            if (sc.td.kind == DRESSI_TEX_2D_ARRAY) layer = sc.td.tri_layer[t];
+        }
+    }
+    const bool oka = !(v0 < 0 || v0 >= sc.V || v1 < 0 || v1 >= sc.V || v2 < 0 || v2 >= sc.V);
+    const bool oku = TEX && !(u0 < 0 || u0 >= sc.Vuv || u1 < 0 || u1 >= sc.Vuv || u2 < 0 || u2 >= sc.Vuv);
     const float w2 = 1.0f - w.x - w.y;
-    int v0, v1, v2;
     float ga[CV];
-    if (tri_corners(sc.tris, sc.T, sc.V, t, v0, v1, v2)) {
-        const float *a0 = sc.vattr + (int64_t)v0 * CV, *a1 = sc.vattr + (int64_t)v1 * CV,
-                    *a2 = sc.vattr + (int64_t)v2 * CV;
+    float smp[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    float q[2] = {0.0f, 0.0f};
+    // The attribute and coordinate rows are loaded without a branch (from row
+    // 0 for an invalid corner, whose result is then replaced by zero), so that
+    // all their loads are in flight together.
+    if (sc.V > 0 && (!TEX || sc.Vuv > 0)) {
+        const float *a0 = sc.vattr + (int64_t)(oka ? v0 : 0) * CV, *a1 = sc.vattr + (int64_t)(oka ? v1 : 0) * CV,
+                    *a2 = sc.vattr + (int64_t)(oka ? v2 : 0) * CV;
+        float A0[CV], A1[CV], A2[CV];
 #pragma unroll
-        for (int c = 0; c < CV; c++) ga[c] = w.x * a0[c] + w.y * a1[c] + w2 * a2[c];
+        for (int c = 0; c < CV; c++) {
+            A0[c] = a0[c];
+            A1[c] = a1[c];
+            A2[c] = a2[c];
+        }
+        float P0[2] = {0.0f, 0.0f}, P1[2] = {0.0f, 0.0f}, P2[2] = {0.0f, 0.0f};
+        if (TEX) {
+            const float *p0 = sc.uv + 2 * (int64_t)(oku ? u0 : 0), *p1 = sc.uv + 2 * (int64_t)(oku ? u1 : 0),
+                        *p2 = sc.uv + 2 * (int64_t)(oku ? u2 : 0);
+#pragma unroll
+            for (int c = 0; c < 2; c++) {
+                P0[c] = p0[c];
+                P1[c] = p1[c];
+                P2[c] = p2[c];
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < CV; c++) ga[c] = oka ? w.x * A0[c] + w.y * A1[c] + w2 * A2[c] : 0.0f;
+        if (TEX) {
+#pragma unroll
+            for (int c = 0; c < 2; c++) q[c] = oku ? w.x * P0[c] + w.y * P1[c] + w2 * P2[c] : 0.0f;
+        }
     } else {
 #pragma unroll
         for (int c = 0; c < CV; c++) ga[c] = 0.0f;
     }
-#pragma unroll
-    for (int c = 0; c < CV; c++) gbuf[i * CV + c] = ga[c];
-    float smp[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    // the camera beside the taps (shading needs it last)
+    if (view) {
+        const int64_t e = sc.tri_eye ? (int64_t)sc.tri_eye[t] : i / npix;
+        eye[0] = sc.eye[3 * e]; eye[1] = sc.eye[3 * e + 1]; eye[2] = sc.eye[3 * e + 2];
+    }
     if (TEX) {
-        float q[2] = {0.0f, 0.0f};
-        if (tri_corners(sc.uv_tris, sc.T, sc.Vuv, t, v0, v1, v2)) {
-            const float *u0 = sc.uv + 2 * (int64_t)v0, *u1 = sc.uv + 2 * (int64_t)v1, *u2 = sc.uv + 2 * (int64_t)v2;
-#pragma unroll
-            for (int c = 0; c < 2; c++) q[c] = w.x * u0[c] + w.y * u1[c] + w2 * u2[c];
-        }
-        uvbuf[2 * i] = q[0];
-        uvbuf[2 * i + 1] = q[1];
-        const Taps tp = make_taps(sc.td, q, tex_layer(sc.td, tri_id, i));
+        const Taps tp = make_taps(sc.td, q, layer);
         if (tp.ok) tex_bilinear<4>(sc.tex, sc.td, tp, smp, 4);
-        reinterpret_cast<float4 *>(samp)[i] = make_float4(smp[0], smp[1], smp[2], smp[3]);
     }
     dressi_frag_in in{};
     in.normal = ga;
     in.pos = ga + 3;
     in.albedo = TEX ? smp : ga + 6;
     in.albedo_channels = TEX ? 4 : 3;
-    const int64_t e = sc.tri_eye ? (int64_t)sc.tri_eye[t] : i / npix;
     ShadeState s;
-    shade_forward(mode, in, sc.eye + 3 * e, 0, mode != DRESSI_SHADE_LAMBERT, s);
+    shade_forward(mode, in, eye, 0, view, s);
+    edge[i] = 0;
+#pragma unroll
+    for (int c = 0; c < CV; c++) gbuf[i * CV + c] = ga[c];
+    if (TEX) {
+        uvbuf[2 * i] = q[0];
+        uvbuf[2 * i + 1] = q[1];
+        reinterpret_cast<float4 *>(samp)[i] = make_float4(smp[0], smp[1], smp[2], smp[3]);
+    }
     shade_color(mode, s, color + 3 * i);
     sil[i] = 1.0f;
 }
@@ -1078,12 +1122,12 @@ __global__ void __launch_bounds__(256)
         const float w = weight ? weight[i] : w_uniform;
         acc += weight ? w * sq : sq;
         const float g0 = 2.0f * w * d0, g1 = 2.0f * w * d1, g2 = 2.0f * w * d2;
-        if (grad_color) {
-            grad_color[3 * i] = g0; grad_color[3 * i + 1] = g1; grad_color[3 * i + 2] = g2;
-        }
-        if (grad_sil) grad_sil[i] = 2.0f * w * d3_;
         const int t = tri_id[i];
         if (t < 0) {
+            if (grad_color) {
+                grad_color[3 * i] = g0; grad_color[3 * i + 1] = g1; grad_color[3 * i + 2] = g2;
+            }
+            if (grad_sil) grad_sil[i] = 2.0f * w * d3_;
             if (!skip_empty) {
                 if (g_gbuf) {
 #pragma unroll
@@ -1094,61 +1138,116 @@ __global__ void __launch_bounds__(256)
                     if (g_bary_uv) g_bary_uv[i] = make_float2(0.0f, 0.0f);
                 }
             }
-        } else {
-            // the hard blend passes the colour gradient to the front layer unchanged
-            dressi_frag_in in{};
-            in.normal = gbuf; in.normal_stride = CV;
-            in.pos = gbuf + 3; in.pos_stride = CV;
-            in.albedo = TEX ? samp : gbuf + 6;
-            in.albedo_stride = TEX ? 4 : CV;
-            in.albedo_channels = TEX ? 4 : 3;
-            const int64_t e = sc.tri_eye ? (int64_t)sc.tri_eye[t] : i / npix;
-            ShadeState s;
-            shade_forward(mode, in, sc.eye + 3 * e, i, mode != DRESSI_SHADE_LAMBERT, s);
-            // without g_gbuf only the albedo sample's gradient (texture-only steps)
-            dressi_frag_grad gr{};
-            if (g_gbuf) {
-                gr.normal = g_gbuf; gr.normal_stride = CV;
-                gr.pos = g_gbuf + 3; gr.pos_stride = CV;
-            }
-            gr.albedo = TEX ? g_samp : (g_gbuf ? g_gbuf + 6 : nullptr);
-            gr.albedo_stride = TEX ? 4 : CV;
-            shade_bwd_frag(mode, in, s, d3{g0, g1, g2}, nullptr, gr, i, g_gbuf != nullptr);
-            if (TEX && (inv || g_bary_uv || rec)) {
-                const float q[2] = {uvbuf[2 * i], uvbuf[2 * i + 1]};
-                const Taps tp = make_taps(sc.td, q, tex_layer(sc.td, tri_id, i));
-                float du = 0.0f, dv = 0.0f;
-                if (tp.ok && inv) {
-                    const int cx = cell1d(q[0], sc.td.Wt, sc.td.wrap_u);
-                    const int cy = cell1d(q[1], sc.td.Ht, sc.td.wrap_v);
-                    const int64_t sl = i / npix;
-                    const int64_t cells = (int64_t)tex_faces(sc.td) * sc.td.Ht * sc.td.Wt;
-                    atomicMax(&inv[sl * cells + ((int64_t)tp.face * sc.td.Ht + cy) * sc.td.Wt + cx],
-                              (int)(i - sl * npix));
-                }
-                if (tp.ok && (g_bary_uv || rec)) {
-                    float gs[4];
-                    ldv<4>(g_samp + 4 * i, gs, 4);
-                    if (g_bary_uv) tex_dcoord<4>(sc.tex, sc.td, tp, gs, 4, du, dv);
-                    if (rec) invrec_put(rec + 2 * i, tp, gs);
-                }
-                // barycentric adjoint of the interpolated coordinate
-                float2 gb = make_float2(0.0f, 0.0f);
-                int v0, v1, v2;
-                if (tri_corners(sc.uv_tris, sc.T, sc.Vuv, t, v0, v1, v2)) {
-                    const float *u0 = sc.uv + 2 * (int64_t)v0, *u1 = sc.uv + 2 * (int64_t)v1,
-                                *u2 = sc.uv + 2 * (int64_t)v2;
-                    const float gq[2] = {du, dv};
-                    float a = 0.0f, b = 0.0f;
+            continue;
+        }
+        // Every load of the fragment is issued before its first store (the
+        // outputs may alias the inputs as far as the compiler knows, so a
+        // store would hold back each later load): its G-buffer row, sample and
+        // coordinate, its corners' coordinate indices, the texture layer and
+        // the camera; then the corners' coordinates beside the taps' texels.
+        // The shading adjoint writes into registers, stored at the end.
+        const bool view = mode != DRESSI_SHADE_LAMBERT;
+        const bool texg = TEX && (inv || g_bary_uv || rec);
+        float gv[CV];
 #pragma unroll
-                    for (int c = 0; c < 2; c++) {
-                        a += gq[c] * (u0[c] - u2[c]);
-                        b += gq[c] * (u1[c] - u2[c]);
-                    }
-                    gb = make_float2(0.0f + a, 0.0f + b);
+        for (int c = 0; c < CV; c++) gv[c] = gbuf[i * CV + c];
+        float sm[4] = {0.0f, 0.0f, 0.0f, 0.0f}, q[2] = {0.0f, 0.0f};
+        int u0 = -1, u1 = -1, u2 = -1, layer = 0;
+        if (TEX) {
+            const float4 a4 = reinterpret_cast<const float4 *>(samp)[i];
+            sm[0] = a4.x; sm[1] = a4.y; sm[2] = a4.z; sm[3] = a4.w;
+            if (texg) {
+                q[0] = uvbuf[2 * i];
+                q[1] = uvbuf[2 * i + 1];
+                if (t < sc.T) {
+                    const int32_t *ut = sc.uv_tris + 3 * (int64_t)t;
+                    u0 = ut[0]; u1 = ut[1]; u2 = ut[2];
+                    if (sc.td.kind == DRESSI_TEX_2D_ARRAY) layer = sc.td.tri_layer[t];
                 }
-                if (g_bary_uv) g_bary_uv[i] = gb;
             }
+        }
+        // the taps' texels, the corners' coordinates (from row 0 for an
+        // invalid corner, whose result is then zero) and the camera together
+        Taps tp;
+        tp.ok = 0;
+        float t00[4], t01[4], t10[4], t11[4];
+        bool oku = false;
+        float P0[2] = {0.0f, 0.0f}, P1[2] = {0.0f, 0.0f}, P2[2] = {0.0f, 0.0f};
+        if (texg) {
+            tp = make_taps(sc.td, q, layer);
+            if (tp.ok && g_bary_uv) tex_taps_load<4>(sc.tex, sc.td, tp, 4, t00, t01, t10, t11);
+            oku = !(u0 < 0 || u0 >= sc.Vuv || u1 < 0 || u1 >= sc.Vuv || u2 < 0 || u2 >= sc.Vuv);
+            if (sc.Vuv > 0) {
+                const float *p0 = sc.uv + 2 * (int64_t)(oku ? u0 : 0), *p1 = sc.uv + 2 * (int64_t)(oku ? u1 : 0),
+                            *p2 = sc.uv + 2 * (int64_t)(oku ? u2 : 0);
+#pragma unroll
+                for (int c = 0; c < 2; c++) {
+                    P0[c] = p0[c];
+                    P1[c] = p1[c];
+                    P2[c] = p2[c];
+                }
+            }
+        }
+        float eye[3] = {0.0f, 0.0f, 0.0f};
+        if (view) {
+            const int64_t e = sc.tri_eye ? (int64_t)sc.tri_eye[t] : i / npix;
+            eye[0] = sc.eye[3 * e]; eye[1] = sc.eye[3 * e + 1]; eye[2] = sc.eye[3 * e + 2];
+        }
+        // the hard blend passes the colour gradient to the front layer unchanged
+        dressi_frag_in in{};
+        in.normal = gv;
+        in.pos = gv + 3;
+        in.albedo = TEX ? sm : gv + 6;
+        in.albedo_channels = TEX ? 4 : 3;
+        ShadeState s;
+        shade_forward(mode, in, eye, 0, view, s);
+        // without g_gbuf only the albedo sample's gradient (texture-only steps)
+        float lg[CV], gs[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int c = 0; c < CV; c++) lg[c] = 0.0f;
+        dressi_frag_grad gr{};
+        if (g_gbuf) {
+            gr.normal = lg;
+            gr.pos = lg + 3;
+        }
+        gr.albedo = TEX ? gs : (g_gbuf ? lg + 6 : nullptr);
+        shade_bwd_frag(mode, in, s, d3{g0, g1, g2}, nullptr, gr, 0, g_gbuf != nullptr);
+        float2 gb = make_float2(0.0f, 0.0f);
+        if (texg) {
+            float du = 0.0f, dv = 0.0f;
+            if (tp.ok && g_bary_uv) tex_dcoord_texels<4>(sc.td, tp, t00, t01, t10, t11, gs, 4, du, dv);
+            if (tp.ok && inv) {
+                const int cx = cell1d(q[0], sc.td.Wt, sc.td.wrap_u);
+                const int cy = cell1d(q[1], sc.td.Ht, sc.td.wrap_v);
+                const int64_t sl = i / npix;
+                const int64_t cells = (int64_t)tex_faces(sc.td) * sc.td.Ht * sc.td.Wt;
+                atomicMax(&inv[sl * cells + ((int64_t)tp.face * sc.td.Ht + cy) * sc.td.Wt + cx],
+                          (int)(i - sl * npix));
+            }
+            if (tp.ok && rec) invrec_put(rec + 2 * i, tp, gs);
+            // barycentric adjoint of the interpolated coordinate
+            if (oku) {
+                const float gq[2] = {du, dv};
+                float a = 0.0f, b = 0.0f;
+#pragma unroll
+                for (int c = 0; c < 2; c++) {
+                    a += gq[c] * (P0[c] - P2[c]);
+                    b += gq[c] * (P1[c] - P2[c]);
+                }
+                gb = make_float2(0.0f + a, 0.0f + b);
+            }
+        }
+        if (grad_color) {
+            grad_color[3 * i] = g0; grad_color[3 * i + 1] = g1; grad_color[3 * i + 2] = g2;
+        }
+        if (grad_sil) grad_sil[i] = 2.0f * w * d3_;
+        if (g_gbuf) {
+#pragma unroll
+            for (int c = 0; c < CV; c++) g_gbuf[i * CV + c] = lg[c];
+        }
+        if (TEX) {
+            reinterpret_cast<float4 *>(g_samp)[i] = make_float4(gs[0], gs[1], gs[2], gs[3]);
+            if (texg && g_bary_uv) g_bary_uv[i] = gb;
         }
     }
     red[threadIdx.x] = acc;

@@ -165,17 +165,24 @@ __device__ __forceinline__ void tex_bilinear(const float *__restrict__ tex, cons
     for (int c = 0; c < TEX_NC(CT); c++) r[c] = w00 * a[c] + w01 * b[c] + w10 * c4[c] + w11 * d[c];
 }
 
-// d (g . sample) / d (u, v) on the taps' face: the bilinear derivative in the
-// texel grid times the texture's size.
+// The four taps' texels (channels CT, or Ct when CT = 0).
 template <int CT>
-__device__ __forceinline__ void tex_dcoord(const float *__restrict__ tex, const dressi_tex_desc &td,
-                                           const Taps &t, const float *g, int Ct, float &du, float &dv) {
+__device__ __forceinline__ void tex_taps_load(const float *__restrict__ tex, const dressi_tex_desc &td,
+                                              const Taps &t, int Ct, float *p00, float *p01, float *p10,
+                                              float *p11) {
     const int64_t face = (int64_t)t.face * td.Ht * td.Wt;
-    float p00[TEX_NC(CT)], p01[TEX_NC(CT)], p10[TEX_NC(CT)], p11[TEX_NC(CT)];
     ldv<CT>(tex + (face + (int64_t)t.y0 * td.Wt + t.x0) * Ct, p00, Ct);
     ldv<CT>(tex + (face + (int64_t)t.y0 * td.Wt + t.x1) * Ct, p01, Ct);
     ldv<CT>(tex + (face + (int64_t)t.y1 * td.Wt + t.x0) * Ct, p10, Ct);
     ldv<CT>(tex + (face + (int64_t)t.y1 * td.Wt + t.x1) * Ct, p11, Ct);
+}
+
+// d (g . sample) / d (u, v) on the taps' face from its texels: the bilinear
+// derivative in the texel grid times the texture's size.
+template <int CT>
+__device__ __forceinline__ void tex_dcoord_texels(const dressi_tex_desc &td, const Taps &t, const float *p00,
+                                                  const float *p01, const float *p10, const float *p11,
+                                                  const float *g, int Ct, float &du, float &dv) {
     du = 0.0f;
     dv = 0.0f;
 #pragma unroll
@@ -186,4 +193,13 @@ __device__ __forceinline__ void tex_dcoord(const float *__restrict__ tex, const 
     }
     du *= (float)td.Wt;
     dv *= (float)td.Ht;
+}
+
+// The same, loading the texels.
+template <int CT>
+__device__ __forceinline__ void tex_dcoord(const float *__restrict__ tex, const dressi_tex_desc &td,
+                                           const Taps &t, const float *g, int Ct, float &du, float &dv) {
+    float p00[TEX_NC(CT)], p01[TEX_NC(CT)], p10[TEX_NC(CT)], p11[TEX_NC(CT)];
+    tex_taps_load<CT>(tex, td, t, Ct, p00, p01, p10, p11);
+    tex_dcoord_texels<CT>(td, t, p00, p01, p10, p11, g, Ct, du, dv);
 }
