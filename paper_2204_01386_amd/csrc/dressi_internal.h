@@ -278,9 +278,11 @@ void dr_geo_vertex(int Cv, const float *pos, const int32_t *tris, const float *p
 // pixels placed at pixel (ox, oy) of the image (0, 0 for a whole image):
 // coordinates are snapped in the view's own frame, then moved by the integer
 // offset, and the boxes are clamped to the view.  `margin` extends the pixel
-// bbox (soft reach).  cull = 1 drops faces clockwise in NDC.
-__device__ __forceinline__ TriSetup dr_setup(const float4 *pc, int v0, int v1, int v2, int H,
-                                             int W, int ox, int oy, int cull, int margin) {
+// bbox (soft reach).  cull = 1 drops faces clockwise in NDC.  Here from the
+// three vertices' clip-space positions p, already loaded; dr_setup below
+// loads them.
+__device__ __forceinline__ TriSetup dr_setup_pts(const float4 *p, int H, int W, int ox, int oy, int cull,
+                                                 int margin) {
     TriSetup s;
     s.meta = 0;
     s.box0 = 1;      // empty box (x0 = 1 > x1 = 0)
@@ -289,15 +291,9 @@ __device__ __forceinline__ TriSetup dr_setup(const float4 *pc, int v0, int v1, i
     s.zlb = 0;
     s.elen[0] = s.elen[1] = s.elen[2] = 0.0f;
     s.pad[0] = s.pad[1] = 0;
-    const int vid[3] = {v0, v1, v2};
-    float4 p[3];
     int X[3], Y[3];
     float hw = 0.5f * (float)W, hh = 0.5f * (float)H;
-    // The three vertices' tests are combined into one branch, so that their
-    // loads are in flight together rather than one after another's test (the
-    // indices are valid: every caller checks them).
-#pragma unroll
-    for (int i = 0; i < 3; i++) p[i] = pc[vid[i]];
+    // the three vertices' tests are combined into one branch
     bool ok = true;
 #pragma unroll
     for (int i = 0; i < 3; i++) {
@@ -363,6 +359,15 @@ __device__ __forceinline__ TriSetup dr_setup(const float4 *pc, int v0, int v1, i
     s.box1 = y0 | (y1 << 16);
     s.meta |= 1;
     return s;
+}
+
+// dr_setup_pts of vertices v0, v1, v2 of pc, loaded before any test so that
+// their loads are in flight together (the indices are valid: every caller
+// checks them).
+__device__ __forceinline__ TriSetup dr_setup(const float4 *pc, int v0, int v1, int v2, int H, int W, int ox, int oy,
+                                             int cull, int margin) {
+    const float4 p[3] = {pc[v0], pc[v1], pc[v2]};
+    return dr_setup_pts(p, H, W, ox, oy, cull, margin);
 }
 
 // dr_setup of triangle `tv` (three vertex indices), empty when an index is

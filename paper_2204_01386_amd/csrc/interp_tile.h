@@ -33,6 +33,33 @@ __host__ __device__ static inline int ib_stride(int C) { return (C + 2) | 1; }
 // `acc` (gb_in[o] plus g . (a0 - a2), g . (a1 - a2)) and writes it to
 // grad_bary.  Returns false for an empty slot skipped under the empty-slot
 // knob (nothing staged or written).
+// The arithmetic of ib_fragment (CC > 0) from its loaded values: bary w, the
+// output gradient row gv and the corners' attribute rows r0, r1, r2 (used
+// only when ok); acc enters as gb_in[o].
+template <int CC>
+__device__ __forceinline__ void ib_fragment_math(bool ok, int t, float2 w, const float *gv, const float *r0,
+                                                 const float *r1, const float *r2, float *dst, float2 &acc) {
+    if (ok) {
+        dst[0] = w.x;
+        dst[1] = w.y;
+        float g0 = 0.0f, g1 = 0.0f;
+#pragma unroll
+        for (int c = 0; c < CC; c++) {
+            dst[2 + c] = gv[c];
+            g0 += gv[c] * (r0[c] - r2[c]);
+            g1 += gv[c] * (r1[c] - r2[c]);
+        }
+        acc.x += g0;
+        acc.y += g1;
+    } else if (t >= 0) {
+        // a fragment whose attribute triangle is invalid contributes nothing
+        dst[0] = 0.0f;
+        dst[1] = 0.0f;
+#pragma unroll
+        for (int c = 0; c < CC; c++) dst[2 + c] = 0.0f;
+    }
+}
+
 template <int CC>
 __device__ __forceinline__ bool ib_fragment(const float *__restrict__ ab, int Va, int C,
                                             const int32_t *__restrict__ attr_tris, int T, int t, int64_t o,
@@ -49,31 +76,31 @@ __device__ __forceinline__ bool ib_fragment(const float *__restrict__ ab, int Va
     bool ok = v0 >= 0 && v0 < Va && v1 >= 0 && v1 < Va && v2 >= 0 && v2 < Va;
     acc = gb_in ? gb_in[o] : make_float2(0.0f, 0.0f);
     const float *g = grad_out + o * C;
+    if constexpr (CC > 0) {
+        float gv[CC], r0[CC], r1[CC], r2[CC];
+        float2 w = make_float2(0.0f, 0.0f);
+        if (ok) {
+            w = bary[o];
+            ld_row<CC>(g, gv, C);
+            ld_row<CC>(ab + (int64_t)v0 * C, r0, C);
+            ld_row<CC>(ab + (int64_t)v1 * C, r1, C);
+            ld_row<CC>(ab + (int64_t)v2 * C, r2, C);
+        }
+        ib_fragment_math<CC>(ok, t, w, gv, r0, r1, r2, dst, acc);
+        if (grad_bary) grad_bary[o] = acc;
+        return true;
+    }
     if (ok) {
         float2 w = bary[o];
         dst[0] = w.x;
         dst[1] = w.y;
         const float *a0 = ab + (int64_t)v0 * C, *a1 = ab + (int64_t)v1 * C, *a2 = ab + (int64_t)v2 * C;
         float g0 = 0.0f, g1 = 0.0f;
-        if constexpr (CC > 0) {
-            float gv[CC], r0[CC], r1[CC], r2[CC];
-            ld_row<CC>(g, gv, C);
-            ld_row<CC>(a0, r0, C);
-            ld_row<CC>(a1, r1, C);
-            ld_row<CC>(a2, r2, C);
-#pragma unroll
-            for (int c = 0; c < CC; c++) {
-                dst[2 + c] = gv[c];
-                g0 += gv[c] * (r0[c] - r2[c]);
-                g1 += gv[c] * (r1[c] - r2[c]);
-            }
-        } else {
-            for (int c = 0; c < C; c++) {
-                float gc = g[c];
-                dst[2 + c] = gc;
-                g0 += gc * (a0[c] - a2[c]);
-                g1 += gc * (a1[c] - a2[c]);
-            }
+        for (int c = 0; c < C; c++) {
+            float gc = g[c];
+            dst[2 + c] = gc;
+            g0 += gc * (a0[c] - a2[c]);
+            g1 += gc * (a1[c] - a2[c]);
         }
         acc.x += g0;
         acc.y += g1;

@@ -1904,19 +1904,61 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX) __attribute__((amdgpu_waves_p
     const int64_t base = (int64_t)bt * DRESSI_TILE_PIX;
     const int nf = fl.n_frag[bt];
     const int nr = fl.n_rec[bt];
-    sfrag[p] = fl.frag[base + p];
+    const uint16_t fr = fl.frag[base + p];   // into LDS before the barrier (its load overlaps the fragment's)
     const int rs0 = fl.rec_start[base + p];
     const int rs1 = p + 1 < DRESSI_TILE_PIX ? fl.rec_start[base + p + 1] : 0;
     if (x < W && y < H) {
+        // The fragment's loads in two rounds: its corners and viewport beside
+        // its barycentrics, output gradient and incoming barycentric gradient;
+        // then the corners' attribute rows beside their clip-space positions
+        // (row 0 for an invalid corner, then unused).  The arithmetic is that
+        // of ib_fragment and dr_setup.
         const int64_t o = (int64_t)y * W + x;
         const int t = tri_id[o];
-        float2 acc;
-        ib_fragment<CC>(attr, Va, CC, tris, T, t, o, bary, grad_out, gb_in, grad_bary, vals + p * S, skip_empty,
-                        acc);
-        if (t >= 0 && t < T) {
-            const int32_t *tv = tris + 3 * (int64_t)t;
-            const int4 q = dr_viewport(vp, t, H, W);
-            TriSetup s = dr_setup_tri(pos_clip, tv, Va, q.w, q.z, q.x, q.y, cull, 0);
+        const bool tri = t >= 0 && t < T;
+        int v0 = -1, v1 = -1, v2 = -1;
+        int4 q = make_int4(0, 0, W, H);
+        if (tri) {
+            v0 = tris[3 * (int64_t)t];
+            v1 = tris[3 * (int64_t)t + 1];
+            v2 = tris[3 * (int64_t)t + 2];
+            q = dr_viewport(vp, t, H, W);
+        }
+        const bool live = !(skip_empty && t < 0);
+        // set only where live (and read only there), so that no copy at the
+        // branch's end waits for the loads
+        float2 w, acc;
+        float gv[CC];
+        if (live) {
+            w = bary[o];
+            ld_row<CC>(grad_out + o * CC, gv, CC);
+            acc = gb_in ? gb_in[o] : make_float2(0.0f, 0.0f);
+        }
+        const bool ok = v0 >= 0 && v0 < Va && v1 >= 0 && v1 < Va && v2 >= 0 && v2 < Va;
+        float r0[CC], r1[CC], r2[CC];
+        float4 P[3];
+        if (Va > 0) {
+            const int c0 = ok ? v0 : 0, c1 = ok ? v1 : 0, c2 = ok ? v2 : 0;
+            ld_row<CC>(attr + (int64_t)c0 * CC, r0, CC);
+            ld_row<CC>(attr + (int64_t)c1 * CC, r1, CC);
+            ld_row<CC>(attr + (int64_t)c2 * CC, r2, CC);
+            P[0] = pos_clip[c0];
+            P[1] = pos_clip[c1];
+            P[2] = pos_clip[c2];
+        }
+        if (live) {
+            ib_fragment_math<CC>(ok, t, w, gv, r0, r1, r2, vals + p * S, acc);
+            if (grad_bary) grad_bary[o] = acc;
+        }
+        if (tri) {
+            TriSetup s;
+            if (ok) {
+                s = dr_setup_pts(P, q.w, q.z, q.x, q.y, cull, 0);
+            } else {
+                s.meta = 0;
+                s.box0 = s.box1 = 1;
+                s.hbox0 = s.hbox1 = 1;
+            }
             float *dst = rvals + p * 9;
             if (!(s.meta & 1)) {
 #pragma unroll
@@ -1929,6 +1971,7 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX) __attribute__((amdgpu_waves_p
             }
         }
     }
+    sfrag[p] = fr;
     __syncthreads();
     // one record per lane (a tile has at most 256)
     if (p < nr) {

@@ -137,13 +137,17 @@ struct dbl3 {
 // Face normals, their sums and the normalisation run in double (the vertex
 // normal is rounded to float once, at the end): the shading downstream has
 // max(0, .) kinks whose side should not depend on the summation order.
+// the face normal (u x v in double) from the corners' positions pa, pb, pc
+__device__ __forceinline__ dbl3 face_normal_rows(const float *pa, const float *pb, const float *pc) {
+    const double p0x = pa[0], p0y = pa[1], p0z = pa[2];
+    const double ux = pb[0] - p0x, uy = pb[1] - p0y, uz = pb[2] - p0z;
+    const double vx = pc[0] - p0x, vy = pc[1] - p0y, vz = pc[2] - p0z;
+    return dbl3{uy * vz - uz * vy, uz * vx - ux * vz, ux * vy - uy * vx};
+}
 __device__ __forceinline__ dbl3 face_normal_d(const float *pos, const int32_t *tris, int t, int V) {
     const int a = tris[3 * t], b = tris[3 * t + 1], c = tris[3 * t + 2];
     if (a < 0 || a >= V || b < 0 || b >= V || c < 0 || c >= V) return dbl3{0.0, 0.0, 0.0};
-    const double p0x = pos[3 * (int64_t)a], p0y = pos[3 * (int64_t)a + 1], p0z = pos[3 * (int64_t)a + 2];
-    const double ux = pos[3 * (int64_t)b] - p0x, uy = pos[3 * (int64_t)b + 1] - p0y, uz = pos[3 * (int64_t)b + 2] - p0z;
-    const double vx = pos[3 * (int64_t)c] - p0x, vy = pos[3 * (int64_t)c + 1] - p0y, vz = pos[3 * (int64_t)c + 2] - p0z;
-    return dbl3{uy * vz - uz * vy, uz * vx - ux * vz, ux * vy - uy * vx};
+    return face_normal_rows(pos + 3 * (int64_t)a, pos + 3 * (int64_t)b, pos + 3 * (int64_t)c);
 }
 
 // sum of the (area-weighted) normals of the faces around v (every lane of the
@@ -328,45 +332,79 @@ __global__ void __launch_bounds__(256)
         // the attribute gradient, here as the pairs (j, j + 4) of each step:
         // every sum sees its terms in the order of its own kernel.
         for (int j = j0 + lane; j < j1; j += GV_LANES) {
-            const int c = adj.corners[j];
-            const int t = c / 3, i = c - 3 * t;
+            // both corners, then both triangles' list bounds, each pair
+            // loaded together (the second corner from j itself when unused)
             const bool two = lane < 4 && j + 4 < j1;
-            const int c2 = two ? adj.corners[j + 4] : c;
+            const int c = adj.corners[j];
+            const int cb = adj.corners[j + 4 < j1 ? j + 4 : j];
+            const int c2 = two ? cb : c;
+            const int t = c / 3, i = c - 3 * t;
             const int t2 = c2 / 3, i2 = c2 - 3 * t2;
             const int e0 = tt.offsets[t], e1 = tt.offsets[t + 1];
-            const dbl3 f = face_normal_d(pos, tris, t, V);
+            const int f0 = tt.offsets[t2], f1 = tt.offsets[t2 + 1];
+            // the face normal's corner positions, loaded beside the records
+            // and combined after them (row 0 for an invalid corner)
+            const int va = tris[3 * t], vb = tris[3 * t + 1], vc = tris[3 * t + 2];
+            const bool nok = !(va < 0 || va >= V || vb < 0 || vb >= V || vc < 0 || vc >= V);
+            float pa[3], pb[3], pc[3];
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                pa[k] = pos[3 * (int64_t)(nok ? va : 0) + k];
+                pb[k] = pos[3 * (int64_t)(nok ? vb : 0) + k];
+                pc[k] = pos[3 * (int64_t)(nok ? vc : 0) + k];
+            }
+            // triangle t's tile records: its clip-space sum on every lane and,
+            // on lanes 0-3, the attribute sum of corner i; beside them, the
+            // second corner's attribute sum (each sum in its own list order)
+            float a[CC], b[CC];
+#pragma unroll
+            for (int q = 0; q < CC; q++) a[q] = b[q] = 0.0f;
+            double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+            const int n1 = e1 - e0, n2 = two ? f1 - f0 : 0;
+            for (int k = 0; k < n1 || k < n2; k++) {
+                // both lists' entries and their rows loaded without a branch
+                // (entry 0 past a list's end, lanes 4-7 the record's first
+                // attribute slice), then added where they count: the sums
+                // start at +0 and so never hold -0, which makes adding +0 a
+                // no-op
+                const bool in1 = k < n1, in2 = k < n2, at1 = in1 && lane < 4;
+                const int2 ent = tt.entries[in1 ? e0 + k : 0];
+                const int2 ent2 = tt.entries[in2 ? f0 + k : 0];
+                const int64_t rix = (int64_t)ent.x * DRESSI_TILE_PIX + ent.y;
+                const int64_t rix2 = (int64_t)ent2.x * DRESSI_TILE_PIX + ent2.y;
+                const float *pp = ipart + rix * 3 * CC + (lane < 4 ? i * CC : 0);
+                const float *pp2 = ipart + rix2 * 3 * CC + i2 * CC;
+                const float *r = rpart + rix * 9 + 3 * i;
+                float v[CC], v2[CC];
+#pragma unroll
+                for (int q = 0; q < CC; q++) {
+                    v[q] = pp[q];
+                    v2[q] = pp2[q];
+                }
+                const float r0 = r[0], r1 = r[1], r2 = r[2];
+#pragma unroll
+                for (int q = 0; q < CC; q++) {
+                    a[q] += at1 ? v[q] : 0.0f;
+                    b[q] += in2 ? v2[q] : 0.0f;
+                }
+                a0 += in1 ? (double)r0 : 0.0;
+                a1 += in1 ? (double)r1 : 0.0;
+                a2 += in1 ? (double)r2 : 0.0;
+            }
+            if (lane < 4) {
+#pragma unroll
+                for (int q = 0; q < CC; q++) s[q] += a[q];
+            }
+            if (two) {
+#pragma unroll
+                for (int q = 0; q < CC; q++) s[q] += b[q];
+            }
+            const dbl3 f = nok ? face_normal_rows(pa, pb, pc) : dbl3{0.0, 0.0, 0.0};
             nacc.x += f.x;
             nacc.y += f.y;
             nacc.z += f.z;
-            if (lane < 4) {
-#pragma unroll
-                for (int h = 0; h < 2; h++) {
-                    if (h == 1 && !two) break;
-                    const int ih = h ? i2 : i;
-                    const int f0 = h ? tt.offsets[t2] : e0, f1 = h ? tt.offsets[t2 + 1] : e1;
-                    float a[CC];
-#pragma unroll
-                    for (int q = 0; q < CC; q++) a[q] = 0.0f;
-                    for (int e = f0; e < f1; e++) {
-                        const int2 ent = tt.entries[e];
-                        const float *pp = ipart + ((int64_t)ent.x * DRESSI_TILE_PIX + ent.y) * 3 * CC + ih * CC;
-#pragma unroll
-                        for (int q = 0; q < CC; q++) a[q] += pp[q];
-                    }
-#pragma unroll
-                    for (int q = 0; q < CC; q++) s[q] += a[q];
-                }
-            }
             // a triangle without fragments adds nothing (as in k_rast_bwd_vertex)
             if (e0 == e1) continue;
-            double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-            for (int e = e0; e < e1; e++) {
-                const int2 ent = tt.entries[e];
-                const float *r = rpart + ((int64_t)ent.x * DRESSI_TILE_PIX + ent.y) * 9 + 3 * i;
-                a0 += (double)r[0];
-                a1 += (double)r[1];
-                a2 += (double)r[2];
-            }
             const int4 q = dr_viewport(vp, t, H, W);
             const double hw = 0.5 * (double)q.z, hh = 0.5 * (double)q.w;
             gx += (float)(a0 * hw * iw);
