@@ -587,6 +587,23 @@ int dressi_packed_backward(dressi_ctx *ctx, const dressi_packed_scene *scene, co
                            float *grad_samp, float *grad_bary_uv, int32_t *inv, void *inv_rec, float *grad_tex,
                            void *stream);
 
+/* Geometry stages of the forward pass for one hard layer (§3.4.1's vertex
+ * stage, then rasterization by Algorithm 2 with K = 1, r = 0, and the
+ * fragment index of its result): the outputs of dressi_vertex_stage (vattr
+ * [V,C] with C = 9 when extra is given, else 6; pos_clip [B,V,4] for the B
+ * matrices mvp [B,4,4]; vert_view NULL) followed by those of
+ * dressi_rasterize_indexed (tri_id [B,H,W], bary [B,H,W,2], index).  adj:
+ * dressi_adjacency of tris.  With the binless strategy
+ * (DRESSI_TUNE_HARD_RASTER = 3) and adj given, the rasterizer's merge runs in
+ * the vertex stage's launch, each triangle transforming its corners with the
+ * stage's own arithmetic (the same positions, bit for bit); otherwise the
+ * two calls run in sequence.  The caller owns every buffer.  Errors:
+ * DRESSI_EINVAL for B < 1, a null pointer other than extra and adj, or the
+ * sizes dressi_rasterize refuses, with nothing launched. */
+int dressi_geometry_fwd(dressi_ctx *ctx, const float *pos, const int32_t *tris, int V, int T, const float *extra,
+                        const int32_t *adj, const float *mvp, int B, float *vattr, float *pos_clip, int H, int W,
+                        int cull, int32_t *tri_id, float *bary, void *index, void *stream);
+
 /* Geometry adjoints of one image (the reverse pass of §3.4's rasterization,
  * interpolation and vertex stages; B = 1, K = 1, hard: after the packed
  * pass), in three launches: the same values as dressi_interpolate_bwd of

@@ -117,6 +117,7 @@ _SIG = {
     "dressi_adjacency": [_vp, _vp, _i, _i, _vp, _vp],
     "dressi_fragment_index": [_vp, _vp, _i, _i, _i, _i, _i, _vp, _vp],
     "dressi_rasterize_indexed": [_vp, _vp, _vp, _i, _i, _i, _i, _i, _i, _vp, _vp, _vp, _vp],
+    "dressi_geometry_fwd": [_vp, _vp, _vp, _i, _i, _vp, _vp, _vp, _i, _vp, _vp, _i, _i, _i, _vp, _vp, _vp, _vp],
     "dressi_shade": [_vp, _i, _vp, _vp, _vp, _i, _i64, _vp, _vp, _vp],
     "dressi_shade_bwd": [_vp, _i, _vp, _vp, _vp, _i, _i64, _vp, _vp, _vp, _vp],
     "dressi_loss_l2": [_vp, _vp, _vp, _vp, _vp, _i, _i, _i, _vp, _vp, _vp, _vp],

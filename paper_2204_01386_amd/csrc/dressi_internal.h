@@ -269,6 +269,13 @@ __device__ __forceinline__ int4 dr_viewport(const Viewports &vp, int t, int H, i
 // vertex sums, the transform adjoint and the vertex-normal adjoint, writing
 // grad_attr, grad_pos_clip and the world-position gradient grad_pos
 // (grad_pos_t and gacc: scratch of 3V floats each).
+// The vertex stage of B views (vattr [V,C], pos_clip [B,V,4]) and the binless
+// hard rasterizer's merge into the zero-kept per-pixel keys zbuf [B,H,W] in
+// one launch (shade.hip); adj: the vertex -> corner adjacency buffer.
+void dr_vertex_raster_direct(const float *pos, const int32_t *tris, const float *extra, const int32_t *adj, int V,
+                             int C, float *vattr, const float *mvp, int B, float *pos_clip, int T, int H, int W,
+                             int cull, unsigned long long *zbuf, hipStream_t st);
+
 void dr_geo_vertex(int Cv, const float *pos, const int32_t *tris, const float *pos_clip, Viewports vp, int V, int H,
                    int W, TriTiles tt, const float *ipart, const float *rpart, Adjacency adj, const float *mvp,
                    const int32_t *vert_view, float *grad_attr, float *grad_pos_clip, float *grad_pos_t, float *gacc,
@@ -387,6 +394,18 @@ __device__ __forceinline__ TriSetup dr_setup_tri(const float4 *pc, const int32_t
 
 __device__ __forceinline__ int dr_corner(int meta, int i) { return (meta >> (4 + 2 * i)) & 3; }
 
+// Clip-space position M p of object-space point (x, y, z) for a row-major 4x4
+// matrix M: the one expression every transform uses, so that recomputed
+// positions are bitwise those of the transform.
+__device__ __forceinline__ float4 clip_of(const float *M, float x, float y, float z) {
+    float4 o;
+    o.x = M[0] * x + M[1] * y + M[2] * z + M[3];
+    o.y = M[4] * x + M[5] * y + M[6] * z + M[7];
+    o.z = M[8] * x + M[9] * y + M[10] * z + M[11];
+    o.w = M[12] * x + M[13] * y + M[14] * z + M[15];
+    return o;
+}
+
 // Integer products in double.  Snapped coordinates satisfy |X|, |Y| < 2^22
 // before a view's offset (below 2^23 with it) and pixel centres are below
 // 2^23, so every difference is below 2^25, every product or sum of two
@@ -445,4 +464,31 @@ __device__ __forceinline__ float dr_depth(const TriSetup &s, const TE *E) {
     float t2 = l2 * d2;
     float z = s.zn[0] + t1;
     return z + t2;
+}
+
+// The binless hard rasterizer's merge of one set-up triangle t (K = 1): each
+// covered pixel centre of its box with depth in (0, 1) takes the 64-bit
+// maximum of ~(depth bits << 32 | t) in zb (one view, H x W), so that the
+// nearest fragment, then the lowest id, wins.
+__device__ __forceinline__ void dr_direct_merge(const TriSetup &s, int t, int W, unsigned long long *zb) {
+    const int x0 = s.box0 & 0xffff, x1 = s.box0 >> 16, y0 = s.box1 & 0xffff, y1 = s.box1 >> 16;
+    for (int y = y0; y <= y1; y++) {
+        const int py = DRESSI_SUBPIX * y + DRESSI_SUBPIX / 2;
+        for (int x = x0; x <= x1; x++) {
+            const int px = DRESSI_SUBPIX * x + DRESSI_SUBPIX / 2;
+            double E[3];
+            bool in = true;
+#pragma unroll
+            for (int i = 0; i < 3; i++) {
+                E[i] = dr_edge(s.X, s.Y, i, px, py);
+                bool own = (s.meta >> (1 + i)) & 1;
+                in = in && (E[i] > 0 || (E[i] == 0 && own));
+            }
+            if (!in) continue;
+            const float z = dr_depth(s, E);
+            if (!(z > 0.0f && z < 1.0f)) continue;
+            const unsigned long long v = ((unsigned long long)__float_as_uint(0.5f * z) << 32) | (unsigned)t;
+            atomicMax(&zb[(int64_t)y * W + x], ~v);
+        }
+    }
 }

@@ -821,27 +821,7 @@ __global__ void k_raster_direct(const float4 *__restrict__ pos_clip, const int32
     const int b = (int)(gid / T), t = (int)(gid - (int64_t)b * T);
     TriSetup s;
     if (!direct_setup(pos_clip, tris, vp, b, V, t, H, W, cull, s)) return;
-    const int x0 = s.box0 & 0xffff, x1 = s.box0 >> 16, y0 = s.box1 & 0xffff, y1 = s.box1 >> 16;
-    unsigned long long *zb = zbuf + (int64_t)b * H * W;
-    for (int y = y0; y <= y1; y++) {
-        const int py = DRESSI_SUBPIX * y + DRESSI_SUBPIX / 2;
-        for (int x = x0; x <= x1; x++) {
-            const int px = DRESSI_SUBPIX * x + DRESSI_SUBPIX / 2;
-            double E[3];
-            bool in = true;
-#pragma unroll
-            for (int i = 0; i < 3; i++) {
-                E[i] = dr_edge(s.X, s.Y, i, px, py);
-                bool own = (s.meta >> (1 + i)) & 1;
-                in = in && (E[i] > 0 || (E[i] == 0 && own));
-            }
-            if (!in) continue;
-            const float z = dr_depth(s, E);
-            if (!(z > 0.0f && z < 1.0f)) continue;
-            const unsigned long long v = ((unsigned long long)__float_as_uint(0.5f * z) << 32) | (unsigned)t;
-            atomicMax(&zb[(int64_t)y * W + x], ~v);
-        }
-    }
+    dr_direct_merge(s, t, W, zbuf + (int64_t)b * H * W);
 }
 
 __global__ void k_raster_direct_resolve(const float4 *__restrict__ pos_clip, const int32_t *__restrict__ tris,
@@ -1488,6 +1468,11 @@ extern "C" int dressi_fragment_index(dressi_ctx *ctx, const int32_t *tri_id, int
     return dressi_launch_check(ctx, "fragment_index");
 }
 
+struct VertexStageArgs;
+static int direct_indexed(dressi_ctx *ctx, const float *pos_clip, const int32_t *tris, int B, int V, int T, int H,
+                          int W, int cull, int32_t *tri_id, float *bary, void *index, hipStream_t st,
+                          const VertexStageArgs *vs);
+
 extern "C" int dressi_rasterize_indexed(dressi_ctx *ctx, const float *pos_clip, const int32_t *tris, int B, int V,
                                         int T, int H, int W, int cull, int32_t *tri_id, float *bary,
                                         void *index, void *stream) {
@@ -1504,10 +1489,24 @@ extern "C" int dressi_rasterize_indexed(dressi_ctx *ctx, const float *pos_clip, 
         if (rc) return rc;
         return dressi_fragment_index(ctx, tri_id, B, 1, H, W, T, index, stream);
     }
-    // without bins: the per-pixel keys after the record counters, both kept at zero
+    return direct_indexed(ctx, pos_clip, tris, B, V, T, H, W, cull, tri_id, bary, index, st, nullptr);
+}
+
+// The binless path of dressi_rasterize_indexed; with `vs`, the merge runs in
+// the vertex stage's launch (dr_vertex_raster_direct) instead of after it.
+struct VertexStageArgs {
+    const float *pos, *extra, *mvp;
+    const int32_t *adj;
+    int C;
+    float *vattr;
+};
+static int direct_indexed(dressi_ctx *ctx, const float *pos_clip, const int32_t *tris, int B, int V, int T, int H,
+                          int W, int cull, int32_t *tri_id, float *bary, void *index, hipStream_t st,
+                          const VertexStageArgs *vs) {
+    // the per-pixel keys after the record counters, both kept at zero
     const size_t nc = ((size_t)B * T + 1) / 2 * 2;
     const int64_t npx = (int64_t)B * H * W;
-    rc = dressi_scratch(ctx, dressi_fragindex_tmp_bytes(B, 1, H, W, T), st);
+    int rc = dressi_scratch(ctx, dressi_fragindex_tmp_bytes(B, 1, H, W, T), st);
     if (rc) return rc;
     rc = dressi_counters(ctx, nc + 2 * (size_t)npx, st);
     if (rc) return rc;
@@ -1516,7 +1515,10 @@ extern "C" int dressi_rasterize_indexed(dressi_ctx *ctx, const float *pos_clip, 
     const float4 *pc4 = reinterpret_cast<const float4 *>(pos_clip);
     const Viewports vp{nullptr, nullptr};
     const int64_t ntri = (int64_t)B * T;
-    if (ntri > 0)
+    if (vs)
+        dr_vertex_raster_direct(vs->pos, tris, vs->extra, vs->adj, V, vs->C, vs->vattr, vs->mvp, B,
+                                const_cast<float *>(pos_clip), T, H, W, cull, zbuf, st);
+    else if (ntri > 0)
         DR_LAUNCH("k_raster_direct", (k_raster_direct), (int)((ntri + 255) / 256), 256, 0, st, pc4, tris, vp, B, V,
                   T, H, W, cull, zbuf);
     FragLists fl;
@@ -1527,14 +1529,36 @@ extern "C" int dressi_rasterize_indexed(dressi_ctx *ctx, const float *pos_clip, 
     int32_t *qcount = fragindex_qcount(tmp, B, 1, H, W, T);
     float2 *b2 = reinterpret_cast<float2 *>(bary);
     if (T < (1 << 24) - 1)
-        DR_LAUNCH("k_raster_direct_resolve_sort", (k_raster_direct_resolve_sort<uint32_t, 8>), B * nt, DRESSI_TILE_PIX, 0,
-                  st, pc4, tris, vp, B, V, T, H, W, cull, ntx, nt, zbuf, tri_id, b2, fl, counts, qcount);
+        DR_LAUNCH("k_raster_direct_resolve_sort", (k_raster_direct_resolve_sort<uint32_t, 8>), B * nt,
+                  DRESSI_TILE_PIX, 0, st, pc4, tris, vp, B, V, T, H, W, cull, ntx, nt, zbuf, tri_id, b2, fl, counts,
+                  qcount);
     else
         DR_LAUNCH("k_raster_direct_resolve_sort", (k_raster_direct_resolve_sort<unsigned long long, 11>), B * nt,
                   DRESSI_TILE_PIX, 0, st, pc4, tris, vp, B, V, T, H, W, cull, ntx, nt, zbuf, tri_id, b2, fl, counts,
                   qcount);
     fragindex_lists(B, 1, H, W, T, fl, tt, tmp, counts, st);
-    return dressi_launch_check(ctx, "rasterize_indexed");
+    return dressi_launch_check(ctx, vs ? "geometry_fwd" : "rasterize_indexed");
+}
+
+extern "C" int dressi_geometry_fwd(dressi_ctx *ctx, const float *pos, const int32_t *tris, int V, int T,
+                                   const float *extra, const int32_t *adj, const float *mvp, int B, float *vattr,
+                                   float *pos_clip, int H, int W, int cull, int32_t *tri_id, float *bary,
+                                   void *index, void *stream) {
+    if (!ctx) return DRESSI_EINVAL;
+    int rc = check_raster_args(ctx, pos_clip, tris, B, V, T, H, W, 1, 0.0f);
+    if (rc) return rc;
+    if (B < 1) return dressi_fail(ctx, DRESSI_EINVAL, "geometry_fwd: B must be >= 1");
+    if (!pos || !mvp || !vattr || !pos_clip || !tri_id || !bary || !index)
+        return dressi_fail(ctx, DRESSI_EINVAL, "geometry_fwd: null pointer");
+    hipStream_t st = (hipStream_t)stream;
+    if (ctx->hard_raster != 3 || !adj || V == 0) {
+        // the two calls in sequence
+        rc = dressi_vertex_stage(ctx, pos, tris, V, T, extra, adj, mvp, nullptr, B, vattr, pos_clip, stream);
+        if (rc) return rc;
+        return dressi_rasterize_indexed(ctx, pos_clip, tris, B, V, T, H, W, cull, tri_id, bary, index, stream);
+    }
+    const VertexStageArgs vs{pos, extra, mvp, adj, extra ? 9 : 6, vattr};
+    return direct_indexed(ctx, pos_clip, tris, B, V, T, H, W, cull, tri_id, bary, index, st, &vs);
 }
 
 // binary search of triangle t among the sorted records of one tile; returns

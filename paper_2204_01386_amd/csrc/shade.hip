@@ -19,12 +19,7 @@ __global__ void k_transform(const float *__restrict__ pos, const float *__restri
     int b = (int)(gid / V), v = (int)(gid - (int64_t)b * V);
     const float *M = mvp + 16 * (int64_t)(vert_view ? vert_view[v] : b);
     float x = pos[3 * (int64_t)v], y = pos[3 * (int64_t)v + 1], z = pos[3 * (int64_t)v + 2];
-    float4 o;
-    o.x = M[0] * x + M[1] * y + M[2] * z + M[3];
-    o.y = M[4] * x + M[5] * y + M[6] * z + M[7];
-    o.z = M[8] * x + M[9] * y + M[10] * z + M[11];
-    o.w = M[12] * x + M[13] * y + M[14] * z + M[15];
-    out[gid] = o;
+    out[gid] = clip_of(M, x, y, z);
 }
 
 __global__ void k_transform_bwd(const float *__restrict__ mvp, const int32_t *__restrict__ vert_view, int B,
@@ -194,26 +189,19 @@ __global__ void k_vertex_attrs(const float *__restrict__ pos, const int32_t *__r
 // sum its face normals as above; lane j transforms it for the views j, j +
 // VA_LANES, ... (with vert_view, lane 0 for its own view) and lane 0 writes
 // its attribute row.
-__global__ void k_vertex_stage(const float *__restrict__ pos, const int32_t *__restrict__ tris,
-                               const float *__restrict__ extra, Adjacency adj, int V, int C,
-                               float *__restrict__ out, const float *__restrict__ mvp,
-                               const int32_t *__restrict__ vert_view, int B, float4 *__restrict__ pos_clip) {
-    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void vertex_stage(int64_t gid, const float *__restrict__ pos,
+                                             const int32_t *__restrict__ tris, const float *__restrict__ extra,
+                                             const Adjacency &adj, int V, int C, float *__restrict__ out,
+                                             const float *__restrict__ mvp, const int32_t *__restrict__ vert_view,
+                                             int B, float4 *__restrict__ pos_clip) {
     const int v = (int)(gid / VA_LANES), slot = (int)(gid % VA_LANES);
     const bool live = v < V;
     const dbl3 a = vertex_acc(pos, tris, adj, v, V, live, slot);
     if (!live) return;
     const float x = pos[3 * (int64_t)v], y = pos[3 * (int64_t)v + 1], z = pos[3 * (int64_t)v + 2];
     const int nb = vert_view ? 1 : B;
-    for (int b = slot; b < nb; b += VA_LANES) {
-        const float *M = mvp + 16 * (int64_t)(vert_view ? vert_view[v] : b);
-        float4 o;
-        o.x = M[0] * x + M[1] * y + M[2] * z + M[3];
-        o.y = M[4] * x + M[5] * y + M[6] * z + M[7];
-        o.z = M[8] * x + M[9] * y + M[10] * z + M[11];
-        o.w = M[12] * x + M[13] * y + M[14] * z + M[15];
-        pos_clip[(int64_t)b * V + v] = o;
-    }
+    for (int b = slot; b < nb; b += VA_LANES)
+        pos_clip[(int64_t)b * V + v] = clip_of(mvp + 16 * (int64_t)(vert_view ? vert_view[v] : b), x, y, z);
     if (slot != 0) return;
     const double l = sqrt(a.x * a.x + a.y * a.y + a.z * a.z);
     const double il = l > 0.0 ? 1.0 / l : 0.0;
@@ -223,6 +211,64 @@ __global__ void k_vertex_stage(const float *__restrict__ pos, const int32_t *__r
     if (C == 9) {
         o[6] = extra[3 * (int64_t)v]; o[7] = extra[3 * (int64_t)v + 1]; o[8] = extra[3 * (int64_t)v + 2];
     }
+}
+
+__global__ void k_vertex_stage(const float *__restrict__ pos, const int32_t *__restrict__ tris,
+                               const float *__restrict__ extra, Adjacency adj, int V, int C,
+                               float *__restrict__ out, const float *__restrict__ mvp,
+                               const int32_t *__restrict__ vert_view, int B, float4 *__restrict__ pos_clip) {
+    vertex_stage((int64_t)blockIdx.x * blockDim.x + threadIdx.x, pos, tris, extra, adj, V, C, out, mvp, vert_view,
+                 B, pos_clip);
+}
+
+// The vertex stage (B views, no vert_view) and the binless hard rasterizer's
+// merge in one launch: the first `nrb` workgroups merge the (view, triangle)
+// pairs, each lane transforming its triangle's three corners itself with the
+// vertex stage's arithmetic (so that the merge does not wait for the stage's
+// positions and its keys are those of the stored positions); the rest run
+// the vertex stage.
+__global__ void __launch_bounds__(256)
+    k_vertex_raster_direct(const float *__restrict__ pos, const int32_t *__restrict__ tris,
+                           const float *__restrict__ extra, Adjacency adj, int V, int C, float *__restrict__ out,
+                           const float *__restrict__ mvp, int B, float4 *__restrict__ pos_clip, int T, int H, int W,
+                           int cull, unsigned long long *__restrict__ zbuf, int nrb) {
+    if ((int)blockIdx.x >= nrb) {
+        vertex_stage((int64_t)(blockIdx.x - nrb) * blockDim.x + threadIdx.x, pos, tris, extra, adj, V, C, out, mvp,
+                     nullptr, B, pos_clip);
+        return;
+    }
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= (int64_t)B * T) return;
+    const int b = (int)(gid / T), t = (int)(gid - (int64_t)b * T);
+    const int32_t *tv = tris + 3 * (int64_t)t;
+    const int v0 = tv[0], v1 = tv[1], v2 = tv[2];
+    if (v0 < 0 || v0 >= V || v1 < 0 || v1 >= V || v2 < 0 || v2 >= V) return;
+    const float *M = mvp + 16 * (int64_t)b;
+    const int vid[3] = {v0, v1, v2};
+    float q[9];
+#pragma unroll
+    for (int i = 0; i < 3; i++) {
+        q[3 * i] = pos[3 * (int64_t)vid[i]];
+        q[3 * i + 1] = pos[3 * (int64_t)vid[i] + 1];
+        q[3 * i + 2] = pos[3 * (int64_t)vid[i] + 2];
+    }
+    float4 p[3];
+#pragma unroll
+    for (int i = 0; i < 3; i++) p[i] = clip_of(M, q[3 * i], q[3 * i + 1], q[3 * i + 2]);
+    const TriSetup s = dr_setup_pts(p, H, W, 0, 0, cull, 0);
+    if (!(s.meta & 1)) return;
+    dr_direct_merge(s, t, W, zbuf + (int64_t)b * H * W);
+}
+
+void dr_vertex_raster_direct(const float *pos, const int32_t *tris, const float *extra, const int32_t *adj, int V,
+                             int C, float *vattr, const float *mvp, int B, float *pos_clip, int T, int H, int W,
+                             int cull, unsigned long long *zbuf, hipStream_t st) {
+    const int nrb = (int)(((int64_t)B * T + 255) / 256);
+    const int nvb = (int)(((int64_t)V * VA_LANES + 255) / 256);
+    if (nrb + nvb == 0) return;
+    DR_LAUNCH("k_vertex_raster_direct", (k_vertex_raster_direct), nrb + nvb, 256, 0, st, pos, tris, extra,
+              adjacency_view(adj, V), V, C, vattr, mvp, B, reinterpret_cast<float4 *>(pos_clip), T, H, W, cull, zbuf,
+              nrb);
 }
 
 // gradient w.r.t. the un-normalised vertex normal sum

@@ -312,10 +312,18 @@ class Step(_TwoStreams):
         """Transform and rasterization; with `attrs`, the vertex attributes
         in the transform's launch (dressi_vertex_stage); with `index` (one
         hard layer), the fragment index in the rasterization's call
-        (dressi_rasterize_indexed)."""
+        (dressi_rasterize_indexed); with both, all in one call
+        (dressi_geometry_fwd)."""
         h, st = self.ctx.handle, self._s()
         self.ctx.tune(Bd.TUNE_HARD_RASTER, self.hard_raster or 0)
         self.ctx.tune(Bd.TUNE_HYBRID_WEIGHT, self.hybrid_weight)
+        if attrs and index and not self.band:
+            # the vertex stage, rasterization and fragment index in one call
+            self._chk(_lib.dressi_geometry_fwd(h, _p(self.pos), _p(self.tris), self.V, self.T, _p(self.extra),
+                                               _p(self.adj), _p(self.mvp), self.B, _p(self.vattr),
+                                               _p(self.pos_clip), self.H, self.W, 0, _p(self.tri_id),
+                                               _p(self.bary), _p(self.frag_index), st), "geometry_fwd")
+            return
         if attrs:
             self._chk(_lib.dressi_vertex_stage(h, _p(self.pos), _p(self.tris), self.V, self.T, _p(self.extra),
                                                _p(self.adj), _p(self.mvp), None, self.B, _p(self.vattr),

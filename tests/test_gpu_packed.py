@@ -367,3 +367,57 @@ def test_rasterize_indexed_argument_checks(Bd):
     assert lib.dressi_rasterize_indexed(*args) == 0
     torch.cuda.synchronize()
     assert not bool((tid == 7).all())
+
+
+@pytest.mark.parametrize("views", [1, 2])
+def test_geometry_fwd_matches_stage_and_rasterization(Bd, views):
+    """dressi_geometry_fwd writes bitwise the vertex attributes and clip
+    positions of dressi_vertex_stage and the triangle ids, barycentrics and
+    fragment index of dressi_rasterize_indexed, with the binless strategy
+    (its merge inside the vertex stage's launch, transforming the corners
+    itself) and a binned one; the index is compared through the
+    rasterization adjoint it feeds."""
+    import ctypes as C
+    from paper_2204_01386_amd.pipeline import Step, make_target
+    s = _ragged_two_views(11) if views == 2 else scenes.config2(H=96, subdiv=4, tex_size=64)
+    st = Step(s, target=make_target(s))
+    lib, ctx = Bd._lib, st.ctx
+    B, H, W, T, V = st.B, st.H, st.W, st.T, st.V
+    nbytes = int(lib.dressi_fragment_index_bytes(B, 1, H, W, T))
+    g = torch.randn((B, 1, H, W, 2), device="cuda")
+    p = lambda t: C.c_void_p(t.data_ptr()) if t is not None else None
+    outs = []
+    for hr, one in ((3, True), (0, True), (3, False)):
+        ctx.tune(Bd.TUNE_HARD_RASTER, hr)
+        vattr = torch.full_like(st.vattr, 7.0)
+        pc = torch.full_like(st.pos_clip, 7.0)
+        tid = torch.empty((B, 1, H, W), dtype=torch.int32, device="cuda")
+        bary = torch.empty((B, 1, H, W, 2), device="cuda")
+        fi = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        if one:
+            assert lib.dressi_geometry_fwd(ctx.handle, p(st.pos), p(st.tris), V, T, p(st.extra), p(st.adj),
+                                           p(st.mvp), B, p(vattr), p(pc), H, W, 0, p(tid), p(bary), p(fi),
+                                           Bd._stream()) == 0
+        else:
+            assert lib.dressi_vertex_stage(ctx.handle, p(st.pos), p(st.tris), V, T, p(st.extra), p(st.adj),
+                                           p(st.mvp), None, B, p(vattr), p(pc), Bd._stream()) == 0
+            assert lib.dressi_rasterize_indexed(ctx.handle, p(pc), p(st.tris), B, V, T, H, W, 0, p(tid), p(bary),
+                                                p(fi), Bd._stream()) == 0
+        gp = Bd.dressi_rasterize_bwd(pc, st.tris, tid, g, frag_index=fi, adj=st.adj)
+        torch.cuda.synchronize()
+        outs.append([host(x).copy() for x in (vattr, pc, tid, bary, gp)])
+    ctx.tune(Bd.TUNE_HARD_RASTER, 0)
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            assert np.array_equal(a, b)
+    assert (outs[0][2] >= 0).any()
+    # argument checks: EINVAL with nothing launched
+    tid = torch.full((B, 1, H, W), 5, dtype=torch.int32, device="cuda")
+    args = [ctx.handle, p(st.pos), p(st.tris), V, T, p(st.extra), p(st.adj), p(st.mvp), B, p(st.vattr),
+            p(st.pos_clip), H, W, 0, p(tid), p(st.bary), p(fi), Bd._stream()]
+    for i, bad in ((1, None), (7, None), (8, 0), (9, None), (10, None), (11, 0), (14, None), (16, None)):
+        a = list(args)
+        a[i] = bad
+        assert lib.dressi_geometry_fwd(*a) == Bd.EINVAL, (i, bad)
+    torch.cuda.synchronize()
+    assert bool((tid == 5).all())
