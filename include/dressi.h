@@ -629,6 +629,42 @@ int dressi_geometry_bwd(dressi_ctx *ctx, const float *pos, const float *vattr, i
                         const float *grad_bary_in, const void *frag_index, const int32_t *adj, float *grad_vattr,
                         float *grad_bary, float *grad_pos_clip, float *grad_pos, void *stream);
 
+/* One whole packed step of one image (§3.3.4: the step as one recorded
+ * sequence; B = 1, K = 1, hard blend, r = 0): dressi_geometry_fwd (mvp one
+ * matrix, cull 0), dressi_packed_forward, dressi_packed_backward (weight
+ * NULL, grad_color and grad_sil not written; Phong: the texel gradient from
+ * the pixel records, inv_rec and grad_tex required) and dressi_geometry_bwd
+ * (no viewports; grad_bary_in = grad_bary_uv when textured), the same values
+ * as those calls in that order.  Because the library sees the whole step it
+ * can launch independent kernels of different stages together: the
+ * fragment index's triangle -> tile lists are built in the launches of the
+ * shading passes, the texel gather and the per-tile geometry adjoint.
+ * scene->vattr must be b->vattr (written by the step).  Every buffer is the
+ * caller's; EINVAL as the four calls refuse their arguments, with nothing
+ * launched. */
+typedef struct {
+    const float *pos;        /* [V,3] world positions */
+    const float *extra;      /* [V,3] vertex colour (Lambert, Cv = 9) or NULL */
+    const int32_t *adj;      /* dressi_adjacency of scene->tris */
+    const float *mvp;        /* [4,4] */
+    int H, W;
+    const float *target;     /* [H,W,4] */
+    /* forward values (written) */
+    float *vattr, *pos_clip;
+    int32_t *tri_id;
+    float *bary;
+    void *index;             /* dressi_fragment_index_bytes(1, 1, H, W, T) */
+    float *gbuf, *uvbuf, *samp, *color, *sil;
+    uint8_t *edge;
+    int32_t *inv;
+    void *inv_rec;
+    /* gradients (written) */
+    float *loss, *grad_gbuf, *grad_samp, *grad_bary_uv, *grad_tex;
+    float *grad_vattr, *grad_bary, *grad_pos_clip, *grad_pos;
+} dressi_packed_step_bufs;
+int dressi_packed_step(dressi_ctx *ctx, const dressi_packed_scene *scene, const dressi_packed_step_bufs *b,
+                       void *stream);
+
 /* ----------------------------------------------------------------------------
  * The optimisation loop around the step (§4.1: vertex positions fitted to
  * silhouettes under a scheduled Laplacian regulariser, then the albedo

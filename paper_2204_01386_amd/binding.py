@@ -59,6 +59,17 @@ class PackedScene(C.Structure):
                 ("tri_eye", _vp)]
 
 
+class PackedStepBufs(C.Structure):
+    """dressi_packed_step_bufs: the inputs, forward values and gradients of
+    one packed step (dressi_packed_step)."""
+    _fields_ = [("pos", _vp), ("extra", _vp), ("adj", _vp), ("mvp", _vp), ("H", _i), ("W", _i), ("target", _vp),
+                ("vattr", _vp), ("pos_clip", _vp), ("tri_id", _vp), ("bary", _vp), ("index", _vp),
+                ("gbuf", _vp), ("uvbuf", _vp), ("samp", _vp), ("color", _vp), ("sil", _vp), ("edge", _vp),
+                ("inv", _vp), ("inv_rec", _vp),
+                ("loss", _vp), ("grad_gbuf", _vp), ("grad_samp", _vp), ("grad_bary_uv", _vp), ("grad_tex", _vp),
+                ("grad_vattr", _vp), ("grad_bary", _vp), ("grad_pos_clip", _vp), ("grad_pos", _vp)]
+
+
 class FragGrad(C.Structure):
     _fields_ = [("normal", _vp), ("normal_stride", _i), ("pos", _vp), ("pos_stride", _i),
                 ("tangent", _vp), ("tangent_stride", _i), ("nmap", _vp), ("nmap_stride", _i),
@@ -117,6 +128,7 @@ _SIG = {
     "dressi_adjacency": [_vp, _vp, _i, _i, _vp, _vp],
     "dressi_fragment_index": [_vp, _vp, _i, _i, _i, _i, _i, _vp, _vp],
     "dressi_rasterize_indexed": [_vp, _vp, _vp, _i, _i, _i, _i, _i, _i, _vp, _vp, _vp, _vp],
+    "dressi_packed_step": [_vp, _vp, _vp, _vp],
     "dressi_geometry_fwd": [_vp, _vp, _vp, _i, _i, _vp, _vp, _vp, _i, _vp, _vp, _i, _i, _i, _vp, _vp, _vp, _vp],
     "dressi_shade": [_vp, _i, _vp, _vp, _vp, _i, _i64, _vp, _vp, _vp],
     "dressi_shade_bwd": [_vp, _i, _vp, _vp, _vp, _i, _i64, _vp, _vp, _vp, _vp],

@@ -2185,3 +2185,27 @@ extern "C" size_t dressi_scratch_bytes(int B, int V, int T, int H, int W, int K,
     }
     return need;
 }
+
+extern "C" int dressi_packed_step(dressi_ctx *ctx, const dressi_packed_scene *sc, const dressi_packed_step_bufs *b,
+                                  void *stream) {
+    if (!ctx) return DRESSI_EINVAL;
+    if (!sc || !b) return dressi_fail(ctx, DRESSI_EINVAL, "packed_step: null scene or buffers");
+    if (sc->vattr != b->vattr) return dressi_fail(ctx, DRESSI_EINVAL, "packed_step: scene->vattr must be b->vattr");
+    const bool tex = sc->mode == DRESSI_SHADE_PHONG;
+    if (tex && (!b->inv || !b->inv_rec || !b->grad_tex))
+        return dressi_fail(ctx, DRESSI_EINVAL, "packed_step: the textured step needs inv, inv_rec and grad_tex");
+    const int V = sc->V, T = sc->T, H = b->H, W = b->W, Cv = sc->Cv;
+    int rc = dressi_geometry_fwd(ctx, b->pos, sc->tris, V, T, b->extra, b->adj, b->mvp, 1, b->vattr, b->pos_clip,
+                                 H, W, 0, b->tri_id, b->bary, b->index, stream);
+    if (rc) return rc;
+    rc = dressi_packed_forward(ctx, sc, b->tri_id, b->bary, 1, H, W, b->gbuf, b->uvbuf, b->samp, b->color, b->sil,
+                               b->edge, b->inv, stream);
+    if (rc) return rc;
+    rc = dressi_packed_backward(ctx, sc, b->tri_id, 1, H, W, b->gbuf, b->uvbuf, b->samp, b->color, b->sil,
+                                b->target, nullptr, b->loss, nullptr, nullptr, b->grad_gbuf, b->grad_samp,
+                                b->grad_bary_uv, b->inv, b->inv_rec, b->grad_tex, stream);
+    if (rc) return rc;
+    return dressi_geometry_bwd(ctx, b->pos, b->vattr, V, Cv, sc->tris, T, b->pos_clip, b->mvp, nullptr, nullptr,
+                               nullptr, 0, H, W, 0, b->tri_id, b->bary, b->grad_gbuf, tex ? b->grad_bary_uv : nullptr,
+                               b->index, b->adj, b->grad_vattr, b->grad_bary, b->grad_pos_clip, b->grad_pos, stream);
+}

@@ -306,6 +306,9 @@ class Step(_TwoStreams):
         self.hybrid_weight = HYBRID_WEIGHT_DEFAULT
         # one hard layer: the fragment index built in the rasterization's call
         self.fuse_index = True
+        # one view, packed: the whole step as one call (dressi_packed_step)
+        self.whole_step = True
+        self._step_bufs = None
         self._calibrate_bins()
 
     def _raster(self, attrs=False, index=False):
@@ -549,11 +552,42 @@ class Step(_TwoStreams):
                                         _p(self.g_vattr), _p(self.g_pos_t), _p(self.g_pos), s),
            "vertex_attrs_bwd")
 
+    def _whole_step(self):
+        """One view, one hard layer in the packed form, every stage on the
+        caller's stream: the whole step as one call (dressi_packed_step, the
+        same values as the calls of forward() and the packed backward), so
+        that the library can launch independent kernels of different stages
+        together.  Returns False where it does not apply."""
+        if not (self.whole_step and self.packed_geo and self.frame == 0 and self.fuse_index and self.r == 0
+                and not self.band and self.concurrent is False and (self.uv is None or self.gather_rec)):
+            return False
+        if self._step_bufs is None:
+            b = Bd.PackedStepBufs()
+            b.pos, b.extra, b.adj, b.mvp = _p(self.pos), _p(self.extra), _p(self.adj), _p(self.mvp)
+            b.H, b.W, b.target = self.H, self.W, _p(self.target)
+            b.vattr, b.pos_clip, b.tri_id, b.bary = _p(self.vattr), _p(self.pos_clip), _p(self.tri_id), _p(self.bary)
+            b.index, b.gbuf, b.uvbuf, b.samp = _p(self.frag_index), _p(self.gbuf), _p(self.uvbuf), _p(self.samp)
+            b.color, b.sil, b.edge, b.inv, b.inv_rec = (_p(self.color), _p(self.sil), _p(self.E), _p(self.inv),
+                                                        _p(self.inv_rec))
+            b.loss, b.grad_gbuf, b.grad_samp = _p(self.loss), _p(self.g_gbuf), _p(self.g_samp)
+            b.grad_bary_uv, b.grad_tex = _p(self.g_bary_uv), _p(self.g_tex if self.uv is not None else None)
+            b.grad_vattr, b.grad_bary, b.grad_pos_clip, b.grad_pos = (_p(self.g_vattr), _p(self.g_bary),
+                                                                      _p(self.g_clip), _p(self.g_pos))
+            self._step_bufs = b
+        self.ctx.tune(Bd.TUNE_HARD_RASTER, self.hard_raster or 0)
+        self.ctx.tune(Bd.TUNE_HYBRID_WEIGHT, self.hybrid_weight)
+        with self._sparse():
+            self._chk(_lib.dressi_packed_step(self.ctx.handle, C.byref(self._pscene), C.byref(self._step_bufs),
+                                              self._s()), "packed_step")
+        return True
+
     def run(self):
         """One full step: forward, loss and gradient, backward.  In the packed
         form (and without inverse-UV jitter) the loss and the backward are one
         pass, which leaves g_color and g_sil unwritten."""
         packed = self.packed and self.frame == 0
+        if packed and self._whole_step():
+            return
         self.forward()
         if packed:
             with self._sparse():

@@ -421,3 +421,62 @@ def test_geometry_fwd_matches_stage_and_rasterization(Bd, views):
         assert lib.dressi_geometry_fwd(*a) == Bd.EINVAL, (i, bad)
     torch.cuda.synchronize()
     assert bool((tid == 5).all())
+
+
+@pytest.mark.parametrize("which", ["config1", "config2"])
+@pytest.mark.parametrize("hr", [0, 3])
+def test_packed_step_matches_its_calls(Bd, which, hr):
+    """dressi_packed_step gives bitwise the forward values, the loss and
+    every gradient of the separate calls it stands for (geometry forward,
+    packed forward and backward, geometry adjoints), with the binless and a
+    binned rasterizer, eagerly and over graph replays."""
+    from paper_2204_01386_amd.pipeline import Step, make_target
+    s = _scene(which)
+    res = []
+    for whole in (False, True):
+        st = Step(s, target=make_target(s))
+        st.whole_step = whole
+        st.hard_raster = hr
+        st.run()
+        torch.cuda.synchronize()
+        assert st._step_bufs is None if not whole else st._step_bufs is not None
+        out = {k: host(v).copy() for k, v in st.grads().items()}
+        for k in ("tri_id", "bary", "color", "sil", "pos_clip", "vattr", "loss"):
+            out["fwd_" + k] = host(getattr(st, k)).copy()
+        # the G-buffer at covered pixels (empty slots are left unwritten)
+        out["fwd_gbuf"] = host(st.gbuf).reshape(-1, st.Cv)[host(st.tri_id).reshape(-1) >= 0].copy()
+        res.append(out)
+        if whole:
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g):
+                st.run()
+            for _ in range(3):
+                g.replay()
+                torch.cuda.synchronize()
+                for k, v in st.grads().items():
+                    assert np.array_equal(host(v), out[k]), k
+    for k in res[0]:
+        assert np.array_equal(res[0][k], res[1][k]), k
+
+
+def test_packed_step_argument_checks(Bd):
+    """EINVAL, with nothing launched, for null buffers or a scene whose vattr
+    is not the step's."""
+    import ctypes as C
+    from paper_2204_01386_amd.pipeline import Step, make_target
+    s = scenes.config2(H=32, subdiv=2, tex_size=32)
+    st = Step(s, target=make_target(s))
+    assert st._whole_step()
+    torch.cuda.synchronize()
+    lib, ctx = Bd._lib, st.ctx
+    b = st._step_bufs
+    before = host(st.g_pos).copy()
+    assert lib.dressi_packed_step(ctx.handle, None, C.byref(b), Bd._stream()) == Bd.EINVAL
+    assert lib.dressi_packed_step(ctx.handle, C.byref(st._pscene), None, Bd._stream()) == Bd.EINVAL
+    for f in ("vattr", "inv_rec", "grad_tex"):
+        keep = getattr(b, f)
+        setattr(b, f, None)
+        assert lib.dressi_packed_step(ctx.handle, C.byref(st._pscene), C.byref(b), Bd._stream()) == Bd.EINVAL, f
+        setattr(b, f, keep)
+    torch.cuda.synchronize()
+    assert np.array_equal(host(st.g_pos), before)
