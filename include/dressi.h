@@ -640,8 +640,11 @@ int dressi_geometry_bwd(dressi_ctx *ctx, const float *pos, const float *vattr, i
  * fragment index's triangle -> tile lists are built in the launches of the
  * shading passes, the texel gather and the per-tile geometry adjoint.
  * scene->vattr must be b->vattr (written by the step).  Every buffer is the
- * caller's; EINVAL as the four calls refuse their arguments, with nothing
- * launched. */
+ * caller's.  Errors: DRESSI_EINVAL, with nothing launched, for a null scene
+ * or buffer set, a scene->vattr other than b->vattr or a textured step
+ * without inv, inv_rec and grad_tex; otherwise the code of the first of the
+ * four calls that refuses its arguments (the calls before it have run, and
+ * the fragment index is complete). */
 typedef struct {
     const float *pos;        /* [V,3] world positions */
     const float *extra;      /* [V,3] vertex colour (Lambert, Cv = 9) or NULL */

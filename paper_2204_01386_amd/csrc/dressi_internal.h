@@ -32,6 +32,10 @@ struct dressi_ctx {
     // (and the counters zero) until dressi_destroy.
     std::vector<void *> retired;
     std::string err;
+    // list-building jobs for the next capable launches, taken in order (a
+    // whole step only)
+    const struct ListJob *list_job = nullptr;
+    int n_list_jobs = 0;
 };
 
 // ---------------------------------------------------------------------------
@@ -54,6 +58,7 @@ void dressi_edge_mask(const int32_t *tri_id, const float *dist, int B, int K, in
 size_t dr_need_raster(const dressi_limits &l, int64_t cap);   // raster.hip
 size_t dr_need_interp(const dressi_limits &l);                // interp.hip
 size_t dr_need_texture(const dressi_limits &l);               // texture.hip
+size_t dr_packed_bwd_scratch(const dressi_packed_scene *sc, int B, int H, int W, bool grad_tex);
 size_t dr_need_shade(const dressi_limits &l);                 // shade.hip
 size_t dr_need_optim(const dressi_limits &l);                 // optim.hip
 size_t dr_need_pbs(const dressi_limits &l);                   // pbs.hip
@@ -130,8 +135,9 @@ __device__ __forceinline__ void loss_sum_block(const LossJob &j, float *red) {
 // Texel gather from per-pixel records (texture.hip), with an optional loss
 // job in an extra workgroup of its launch; part: scratch of
 // dressi_invuv_part_bytes(cells, 4, S).
+struct ListJob;
 void dr_gather_invrec(const dressi_tex_desc &td, int S, int64_t npix, const int32_t *inv, const int4 *rec,
-                      float *part, float *grad_tex, hipStream_t st, int rows, LossJob lj);
+                      float *part, float *grad_tex, hipStream_t st, int rows, LossJob lj, const ListJob &job);
 
 // Bump allocator over the arena: carve(n) returns 256-byte aligned offsets.
 struct Carver {
@@ -213,6 +219,213 @@ __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb) {
     return x * q + (x < r ? x : r) + (b >> 3);
 }
 __device__ __forceinline__ int64_t xcd_block() { return xcd_block(blockIdx.x, gridDim.x); }
+
+// ---------------------------------------------------------------------------
+// The workgroup bodies of the kernels that turn the per-tile records of a
+// fragment index into its triangle -> tile lists (the counts' scan, the
+// fill and the ranking; prims.hip and raster.hip), as jobs that the extra
+// workgroups of another stage's launch can run: a whole step launches them
+// beside independent kernels (ListJob; bid, nb: the workgroup and the
+// workgroup count the job is run with).  256 lanes a workgroup.
+// ---------------------------------------------------------------------------
+template <int BS>
+__device__ __forceinline__ int block_exclusive_scan(int v, int &total, int *wsum) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    int x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[wid] = x;
+    __syncthreads();
+    if (wid == 0) {
+        int s = (lane < BS / 64) ? wsum[lane] : 0;
+#pragma unroll
+        for (int o = 1; o < BS / 64; o <<= 1) {
+            int y = __shfl_up(s, o, 64);
+            if (lane >= o) s += y;
+        }
+        if (lane < BS / 64) wsum[lane] = s;
+    }
+    __syncthreads();
+    int base = wid ? wsum[wid - 1] : 0;
+    total = wsum[BS / 64 - 1];
+    __syncthreads();
+    return base + x - v;
+}
+
+#define SCAN_BS 256
+#define SCAN_PER 4
+#define SCAN_CHUNK (SCAN_BS * SCAN_PER)
+#define SCAN_DIRECT_MAX 2048   // chunks the one-pass apply adds up before its own
+#define TT_SHORT 32
+
+// the sum of each chunk of SCAN_CHUNK counts
+__device__ __forceinline__ void scan_reduce_block(const int32_t *in, int64_t n, int32_t *block_sums, int bid) {
+    __shared__ int wsum[SCAN_BS / 64];
+    int64_t base = (int64_t)bid * SCAN_CHUNK + (int64_t)threadIdx.x * SCAN_PER;
+    int s = 0;
+#pragma unroll
+    for (int j = 0; j < SCAN_PER; j++)
+        if (base + j < n) s += in[base + j];
+    int total;
+    block_exclusive_scan<SCAN_BS>(s, total, wsum);
+    if (threadIdx.x == 0) block_sums[bid] = total;
+}
+
+// the exclusive scan of one chunk, after adding up the sums of the chunks
+// before it (nb chunks; the last writes the total to out[n])
+__device__ __forceinline__ void scan_apply_direct_block(const int32_t *in, int32_t *out, int64_t n,
+                                                        const int32_t *block_sums, int bid, int nb) {
+    __shared__ int wsum[SCAN_BS / 64];
+    int pre = 0;
+    for (int j = threadIdx.x; j < bid; j += SCAN_BS) pre += block_sums[j];
+    int offset;
+    block_exclusive_scan<SCAN_BS>(pre, offset, wsum);
+    int64_t base = (int64_t)bid * SCAN_CHUNK + (int64_t)threadIdx.x * SCAN_PER;
+    int v[SCAN_PER];
+    int s = 0;
+#pragma unroll
+    for (int j = 0; j < SCAN_PER; j++) {
+        v[j] = (base + j < n) ? in[base + j] : 0;
+        s += v[j];
+    }
+    int total;
+    int ex = block_exclusive_scan<SCAN_BS>(s, total, wsum) + offset;
+#pragma unroll
+    for (int j = 0; j < SCAN_PER; j++) {
+        if (base + j < n) out[base + j] = ex;
+        ex += v[j];
+    }
+    if (bid == nb - 1 && threadIdx.x == SCAN_BS - 1) out[n] = ex;
+}
+
+// One tile's records into their (view, triangle) lists, unsorted: each takes
+// a slot by counting its list's counter back down (which leaves the counters
+// at zero for the next call); the last entry placed of a list longer than
+// TT_SHORT queues it for the merge sort.  Several views: XCD-aware order
+// (each XCD whole views); one view keeps the default interleave.
+__device__ __forceinline__ void tt_fill_block(const FragLists &fl, int K, int T, int nt,
+                                              const int32_t *__restrict__ offsets, int32_t *__restrict__ counts,
+                                              int2 *__restrict__ entries, int32_t *__restrict__ nlong,
+                                              int64_t *__restrict__ longk, int cap, int bid, int nb) {
+    const int bt = nb > nt ? (int)xcd_block(bid, nb) : bid;
+    const int b = bt / nt;
+    const int64_t base = (int64_t)bt * DRESSI_TILE_PIX * K;
+    const int n = fl.n_rec[bt];
+    for (int r = threadIdx.x; r < n; r += blockDim.x) {
+        int t = fl.rec_tri[base + r];
+        if (t < 0 || t >= T) continue;
+        int64_t bt_t = (int64_t)b * T + t;
+        const int c = atomicSub(&counts[bt_t], 1);
+        int slot = offsets[bt_t] + c - 1;
+        entries[slot] = make_int2(bt, r);
+        if (c == 1 && offsets[bt_t + 1] - offsets[bt_t] > TT_SHORT) {
+            const int q = atomicAdd(nlong, 1);
+            if (q < cap) longk[q] = bt_t;
+        }
+    }
+}
+
+// The lists in ascending tile order.  Short lists: one thread per entry,
+// whose place is the number of its list's entries from lower tiles (a
+// triangle has at most one record per tile).  Long lists: one workgroup per
+// queued list, a bottom-up merge sort by tile from the list's stretch of
+// `unsorted`, ping-ponging between its stretches of `sbuf` and `entries`
+// (runs of width 1, 2, 4, ...; an entry's place in its merged pair of runs
+// is its rank in its own run plus the number of smaller tiles in the other,
+// by binary search).  `unsorted` is only read, so the short lists' threads
+// never see a list being sorted.
+__device__ __forceinline__ void tt_rank_block(const FragLists &fl, int K, int T, int nt,
+                                              const int32_t *__restrict__ offsets,
+                                              const int2 *__restrict__ unsorted, int2 *__restrict__ entries,
+                                              int2 *__restrict__ sbuf, int64_t nkeys,
+                                              const int32_t *__restrict__ nlong, const int64_t *__restrict__ longk,
+                                              int cap, int bid, int nb) {
+    const int nq = min(*nlong, cap);
+    for (int q = bid; q < nq; q += nb) {
+        const int64_t key = longk[q];
+        const int lo = offsets[key], n = offsets[key + 1] - lo;
+        for (int i = threadIdx.x; i < n; i += blockDim.x) sbuf[lo + i] = unsorted[lo + i];
+        __syncthreads();
+        int2 *src = sbuf + lo, *dst = entries + lo;
+        for (int w = 1; w < n; w <<= 1) {
+            for (int i = threadIdx.x; i < n; i += blockDim.x) {
+                const int2 x = src[i];
+                const int r = i / w;
+                const int own = r * w, base = (r & ~1) * w;
+                const int ps = (r ^ 1) * w, pe = min(ps + w, n);
+                int a = ps, z = max(ps, pe);
+                while (a < z) {
+                    const int mid = (a + z) >> 1;
+                    if (src[mid].x < x.x) a = mid + 1;
+                    else z = mid;
+                }
+                dst[base + (i - own) + (a - ps)] = x;
+            }
+            __syncthreads();
+            int2 *tswap = src;
+            src = dst;
+            dst = tswap;
+        }
+        if (src != entries + lo)
+            for (int i = threadIdx.x; i < n; i += blockDim.x) entries[lo + i] = src[i];
+        __syncthreads();
+    }
+    const int64_t total = offsets[nkeys];   // the number of entries (the scan's total)
+    for (int64_t e = (int64_t)bid * blockDim.x + threadIdx.x; e < total; e += (int64_t)nb * blockDim.x) {
+        const int2 ent = unsorted[e];
+        const int t = fl.rec_tri[(int64_t)ent.x * DRESSI_TILE_PIX * K + ent.y];
+        const int64_t key = (int64_t)(ent.x / nt) * T + t;
+        const int lo = offsets[key], hi = offsets[key + 1];
+        if (hi - lo > TT_SHORT) continue;   // a long list, sorted above
+        int rank = 0;
+        for (int j = lo; j < hi; j++) rank += unsorted[j].x < ent.x;
+        entries[lo + rank] = ent;
+    }
+}
+
+enum { LJ_NONE = 0, LJ_SCAN_REDUCE, LJ_SCAN_APPLY, LJ_TT_FILL, LJ_TT_RANK };
+struct ListJob {
+    int kind = LJ_NONE;
+    int nb = 0;                         // workgroups
+    const int32_t *in = nullptr;        // scan: counts [n], sums, offsets [n + 1]
+    int32_t *out = nullptr;
+    int64_t n = 0;
+    int32_t *sums = nullptr;
+    FragLists fl{};                     // lists
+    int K = 1, T = 0, nt = 1, cap = 0;
+    int32_t *counts = nullptr, *nlong = nullptr;
+    int2 *unsorted = nullptr, *entries = nullptr, *sbuf = nullptr;
+    int64_t *longk = nullptr;
+};
+__device__ __forceinline__ void list_job_block(const ListJob &j, int bid) {
+    if (bid >= j.nb) return;
+    switch (j.kind) {
+    case LJ_SCAN_REDUCE: scan_reduce_block(j.in, j.n, j.sums, bid); break;
+    case LJ_SCAN_APPLY: scan_apply_direct_block(j.in, j.out, j.n, j.sums, bid, j.nb); break;
+    case LJ_TT_FILL:
+        tt_fill_block(j.fl, j.K, j.T, j.nt, j.out, j.counts, j.unsorted, j.nlong, j.longk, j.cap, bid, j.nb);
+        break;
+    case LJ_TT_RANK:
+        tt_rank_block(j.fl, j.K, j.T, j.nt, j.out, j.unsorted, j.entries, j.sbuf, j.n, j.nlong, j.longk, j.cap, bid,
+                      j.nb);
+        break;
+    default: break;
+    }
+}
+// the job the step's next capable launch takes (none outside a whole step)
+static inline ListJob dr_take_list_job(dressi_ctx *ctx) {
+    ListJob j;
+    if (ctx->n_list_jobs > 0) {
+        j = *ctx->list_job++;
+        ctx->n_list_jobs--;
+    }
+    return j;
+}
+// runs the jobs not taken yet as launches of their own (raster.hip)
+void dr_flush_list_jobs(dressi_ctx *ctx, hipStream_t st);
 
 __host__ __device__ static inline int tiles_x(int W) { return (W + DRESSI_TILE - 1) / DRESSI_TILE; }
 __host__ __device__ static inline int tiles_y(int H) { return (H + DRESSI_TILE - 1) / DRESSI_TILE; }

@@ -34,50 +34,12 @@ void dressi_fill_f32(float *p, float v, int64_t n, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
-// block-wide exclusive scan for 64-lane wavefronts
+// multi-block exclusive scan (block_exclusive_scan and the chunk bodies are
+// in dressi_internal.h, shared with the whole step's co-launched jobs)
 // ---------------------------------------------------------------------------
-template <int BS>
-__device__ __forceinline__ int block_exclusive_scan(int v, int &total, int *wsum) {
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    int x = v;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        int y = __shfl_up(x, o, 64);
-        if (lane >= o) x += y;
-    }
-    if (lane == 63) wsum[wid] = x;
-    __syncthreads();
-    if (wid == 0) {
-        int s = (lane < BS / 64) ? wsum[lane] : 0;
-#pragma unroll
-        for (int o = 1; o < BS / 64; o <<= 1) {
-            int y = __shfl_up(s, o, 64);
-            if (lane >= o) s += y;
-        }
-        if (lane < BS / 64) wsum[lane] = s;
-    }
-    __syncthreads();
-    int base = wid ? wsum[wid - 1] : 0;
-    total = wsum[BS / 64 - 1];
-    __syncthreads();
-    return base + x - v;
-}
-
-#define SCAN_BS 256
-#define SCAN_PER 4
-#define SCAN_CHUNK (SCAN_BS * SCAN_PER)
-
 __global__ void __launch_bounds__(SCAN_BS) k_scan_reduce(const int32_t *in, int64_t n,
                                                          int32_t *block_sums) {
-    __shared__ int wsum[SCAN_BS / 64];
-    int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK + (int64_t)threadIdx.x * SCAN_PER;
-    int s = 0;
-#pragma unroll
-    for (int j = 0; j < SCAN_PER; j++)
-        if (base + j < n) s += in[base + j];
-    int total;
-    block_exclusive_scan<SCAN_BS>(s, total, wsum);
-    if (threadIdx.x == 0) block_sums[blockIdx.x] = total;
+    scan_reduce_block(in, n, block_sums, (int)blockIdx.x);
 }
 
 // single block: exclusive scan of the block sums in place
@@ -122,30 +84,9 @@ __global__ void __launch_bounds__(SCAN_BS) k_scan_apply(const int32_t *in, int32
 // The same, where each block first adds up the totals of the blocks before
 // it (at most SCAN_DIRECT_MAX of them, from L2) instead of reading a scanned
 // copy: one launch fewer than reduce, scan of the totals, apply.
-#define SCAN_DIRECT_MAX 2048
 __global__ void __launch_bounds__(SCAN_BS) k_scan_apply_direct(const int32_t *in, int32_t *out, int64_t n,
                                                                const int32_t *block_sums) {
-    __shared__ int wsum[SCAN_BS / 64];
-    int pre = 0;
-    for (int j = threadIdx.x; j < (int)blockIdx.x; j += SCAN_BS) pre += block_sums[j];
-    int offset;
-    block_exclusive_scan<SCAN_BS>(pre, offset, wsum);
-    int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK + (int64_t)threadIdx.x * SCAN_PER;
-    int v[SCAN_PER];
-    int s = 0;
-#pragma unroll
-    for (int j = 0; j < SCAN_PER; j++) {
-        v[j] = (base + j < n) ? in[base + j] : 0;
-        s += v[j];
-    }
-    int total;
-    int ex = block_exclusive_scan<SCAN_BS>(s, total, wsum) + offset;
-#pragma unroll
-    for (int j = 0; j < SCAN_PER; j++) {
-        if (base + j < n) out[base + j] = ex;
-        ex += v[j];
-    }
-    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == SCAN_BS - 1) out[n] = ex;
+    scan_apply_direct_block(in, out, n, block_sums, (int)blockIdx.x, (int)gridDim.x);
 }
 
 // whole scan in one workgroup (small n): chunks of 4096 with a running carry

@@ -1294,88 +1294,28 @@ void dressi_fragindex_view(void *base, int B, int K, int H, int W, int T, FragLi
 // ---------------------------------------------------------------------------
 // Lists longer than TT_SHORT entries (a triangle over many tiles) are ordered
 // by a workgroup-wide merge sort instead of per-entry counting (quadratic in
-// the list length); k_tt_fill queues them, at most n / (TT_SHORT + 1).
-#define TT_SHORT 32
+// the list length); k_tt_fill queues them, at most n / (TT_SHORT + 1).  The
+// workgroup bodies are in dressi_internal.h.
 __global__ void k_tt_fill(FragLists fl, int K, int T, int nt, const int32_t *__restrict__ offsets,
                           int32_t *__restrict__ counts, int2 *__restrict__ entries, int32_t *__restrict__ nlong,
                           int64_t *__restrict__ longk, int cap) {
-    // several views: XCD-aware order (each XCD whole views); one view keeps the
-    // default interleave, which balances uneven work over the image
-    const int bt = (int)gridDim.x > nt ? (int)xcd_block() : (int)blockIdx.x;
-    const int b = bt / nt;
-    const int64_t base = (int64_t)bt * DRESSI_TILE_PIX * K;
-    const int n = fl.n_rec[bt];
-    for (int r = threadIdx.x; r < n; r += blockDim.x) {
-        int t = fl.rec_tri[base + r];
-        if (t < 0 || t >= T) continue;
-        int64_t bt_t = (int64_t)b * T + t;
-        // counting back down leaves the counters at zero for the next call
-        const int c = atomicSub(&counts[bt_t], 1);
-        int slot = offsets[bt_t] + c - 1;
-        entries[slot] = make_int2(bt, r);
-        // the list's last entry placed queues a long list, once
-        if (c == 1 && offsets[bt_t + 1] - offsets[bt_t] > TT_SHORT) {
-            const int q = atomicAdd(nlong, 1);
-            if (q < cap) longk[q] = bt_t;
-        }
-    }
+    tt_fill_block(fl, K, T, nt, offsets, counts, entries, nlong, longk, cap, (int)blockIdx.x, (int)gridDim.x);
 }
 
-// Short lists: one thread per entry, whose place in its (view, triangle)'s
-// list is the number of that triangle's entries from lower tiles (a triangle
-// has at most one record per tile, so the tile indices in a list are
-// distinct).  Long lists: one workgroup per queued list, a bottom-up merge
-// sort by tile from the list's stretch of `unsorted`, ping-ponging between
-// its stretches of `sbuf` and `entries` (runs of width 1, 2, 4, ...; an
-// entry's place in its merged pair of runs is its rank in its own run plus
-// the number of smaller tiles in the other, found by binary search).
-// `unsorted` is only read, so the short lists' threads never see a list
-// being sorted.  Either way the lists end in ascending tile order.
 __global__ void k_tt_rank(FragLists fl, int K, int T, int nt, const int32_t *__restrict__ offsets,
                           const int2 *__restrict__ unsorted, int2 *__restrict__ entries, int2 *__restrict__ sbuf,
                           int64_t nkeys, const int32_t *__restrict__ nlong, const int64_t *__restrict__ longk,
                           int cap) {
-    const int nq = min(*nlong, cap);
-    for (int q = blockIdx.x; q < nq; q += gridDim.x) {
-        const int64_t key = longk[q];
-        const int lo = offsets[key], n = offsets[key + 1] - lo;
-        for (int i = threadIdx.x; i < n; i += blockDim.x) sbuf[lo + i] = unsorted[lo + i];
-        __syncthreads();
-        int2 *src = sbuf + lo, *dst = entries + lo;
-        for (int w = 1; w < n; w <<= 1) {
-            for (int i = threadIdx.x; i < n; i += blockDim.x) {
-                const int2 x = src[i];
-                const int r = i / w;
-                const int own = r * w, base = (r & ~1) * w;
-                const int ps = (r ^ 1) * w, pe = min(ps + w, n);
-                int a = ps, z = max(ps, pe);
-                while (a < z) {
-                    const int mid = (a + z) >> 1;
-                    if (src[mid].x < x.x) a = mid + 1;
-                    else z = mid;
-                }
-                dst[base + (i - own) + (a - ps)] = x;
-            }
-            __syncthreads();
-            int2 *tswap = src;
-            src = dst;
-            dst = tswap;
-        }
-        if (src != entries + lo)
-            for (int i = threadIdx.x; i < n; i += blockDim.x) entries[lo + i] = src[i];
-        __syncthreads();
-    }
-    const int64_t total = offsets[nkeys];   // the number of entries (the scan's total)
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const int2 ent = unsorted[e];
-        const int t = fl.rec_tri[(int64_t)ent.x * DRESSI_TILE_PIX * K + ent.y];
-        const int64_t key = (int64_t)(ent.x / nt) * T + t;
-        const int lo = offsets[key], hi = offsets[key + 1];
-        if (hi - lo > TT_SHORT) continue;   // a long list, sorted above
-        int rank = 0;
-        for (int j = lo; j < hi; j++) rank += unsorted[j].x < ent.x;
-        entries[lo + rank] = ent;
+    tt_rank_block(fl, K, T, nt, offsets, unsorted, entries, sbuf, nkeys, nlong, longk, cap, (int)blockIdx.x,
+                  (int)gridDim.x);
+}
+
+__global__ void __launch_bounds__(256) k_list_job(ListJob j) { list_job_block(j, (int)blockIdx.x); }
+
+void dr_flush_list_jobs(dressi_ctx *ctx, hipStream_t st) {
+    while (ctx->n_list_jobs > 0) {
+        const ListJob j = dr_take_list_job(ctx);
+        if (j.nb > 0) DR_LAUNCH("k_list_job", (k_list_job), j.nb, 256, 0, st, j);
     }
 }
 
@@ -1471,7 +1411,7 @@ extern "C" int dressi_fragment_index(dressi_ctx *ctx, const int32_t *tri_id, int
 struct VertexStageArgs;
 static int direct_indexed(dressi_ctx *ctx, const float *pos_clip, const int32_t *tris, int B, int V, int T, int H,
                           int W, int cull, int32_t *tri_id, float *bary, void *index, hipStream_t st,
-                          const VertexStageArgs *vs);
+                          const VertexStageArgs *vs, void *tmp = nullptr, bool lists = true);
 
 extern "C" int dressi_rasterize_indexed(dressi_ctx *ctx, const float *pos_clip, const int32_t *tris, int B, int V,
                                         int T, int H, int W, int cull, int32_t *tri_id, float *bary,
@@ -1502,12 +1442,13 @@ struct VertexStageArgs {
 };
 static int direct_indexed(dressi_ctx *ctx, const float *pos_clip, const int32_t *tris, int B, int V, int T, int H,
                           int W, int cull, int32_t *tri_id, float *bary, void *index, hipStream_t st,
-                          const VertexStageArgs *vs) {
+                          const VertexStageArgs *vs, void *tmp, bool lists) {
     // the per-pixel keys after the record counters, both kept at zero
     const size_t nc = ((size_t)B * T + 1) / 2 * 2;
     const int64_t npx = (int64_t)B * H * W;
-    int rc = dressi_scratch(ctx, dressi_fragindex_tmp_bytes(B, 1, H, W, T), st);
+    int rc = tmp ? DRESSI_OK : dressi_scratch(ctx, dressi_fragindex_tmp_bytes(B, 1, H, W, T), st);
     if (rc) return rc;
+    if (!tmp) tmp = ctx->scratch;
     rc = dressi_counters(ctx, nc + 2 * (size_t)npx, st);
     if (rc) return rc;
     int32_t *counts = ctx->counters;
@@ -1525,7 +1466,6 @@ static int direct_indexed(dressi_ctx *ctx, const float *pos_clip, const int32_t 
     TriTiles tt;
     dressi_fragindex_view(index, B, 1, H, W, T, fl, tt);
     const int ntx = tiles_x(W), nt = ntx * tiles_y(H);
-    void *tmp = ctx->scratch;
     int32_t *qcount = fragindex_qcount(tmp, B, 1, H, W, T);
     float2 *b2 = reinterpret_cast<float2 *>(bary);
     if (T < (1 << 24) - 1)
@@ -1536,7 +1476,7 @@ static int direct_indexed(dressi_ctx *ctx, const float *pos_clip, const int32_t 
         DR_LAUNCH("k_raster_direct_resolve_sort", (k_raster_direct_resolve_sort<unsigned long long, 11>), B * nt,
                   DRESSI_TILE_PIX, 0, st, pc4, tris, vp, B, V, T, H, W, cull, ntx, nt, zbuf, tri_id, b2, fl, counts,
                   qcount);
-    fragindex_lists(B, 1, H, W, T, fl, tt, tmp, counts, st);
+    if (lists) fragindex_lists(B, 1, H, W, T, fl, tt, tmp, counts, st);
     return dressi_launch_check(ctx, vs ? "geometry_fwd" : "rasterize_indexed");
 }
 
@@ -1912,8 +1852,13 @@ __global__ void __launch_bounds__(DRESSI_TILE_PIX) __attribute__((amdgpu_waves_p
                const float4 *__restrict__ pos_clip, Viewports vp, int H, int W, int cull,
                const int32_t *__restrict__ tri_id, const float2 *__restrict__ bary, int ntx, FragLists fl,
                const float *__restrict__ grad_out, const float2 *__restrict__ gb_in, float2 *__restrict__ grad_bary,
-               float *__restrict__ ipart, float *__restrict__ rpart, int skip_empty) {
+               float *__restrict__ ipart, float *__restrict__ rpart, int skip_empty, ListJob lj, int nmain) {
     extern __shared__ float vals[];   // [256][ib_stride(CC)] interpolation rows, then [256][9]
+    // workgroups past the tiles run a list-building job of the step
+    if ((int)blockIdx.x >= nmain) {
+        list_job_block(lj, (int)blockIdx.x - nmain);
+        return;
+    }
     constexpr int S = (CC + 2) | 1;
     float *rvals = vals + DRESSI_TILE_PIX * S;
     __shared__ uint16_t sfrag[DRESSI_TILE_PIX];   // the tile's sorted fragment list
@@ -2070,12 +2015,13 @@ extern "C" int dressi_geometry_bwd(dressi_ctx *ctx, const float *pos, const floa
     float2 *gbo = reinterpret_cast<float2 *>(grad_bary);
     if (nt > 0 && (Cv == 9 || al8)) {
         const size_t lds = sizeof(float) * DRESSI_TILE_PIX * (((Cv + 2) | 1) + 9);
+        const ListJob lj = dr_take_list_job(ctx);
         if (Cv == 6)
-            DR_LAUNCH("k_geo_tile", (k_geo_tile<6>), nt, DRESSI_TILE_PIX, lds, st, vattr, V, tris, T, pc4, vp, H, W,
-                      cull, tri_id, b2, ntx, fl, grad_gbuf, gbi, gbo, ipart, rpart, ctx->skip_empty);
+            DR_LAUNCH("k_geo_tile", (k_geo_tile<6>), nt + lj.nb, DRESSI_TILE_PIX, lds, st, vattr, V, tris, T, pc4, vp,
+                      H, W, cull, tri_id, b2, ntx, fl, grad_gbuf, gbi, gbo, ipart, rpart, ctx->skip_empty, lj, nt);
         else
-            DR_LAUNCH("k_geo_tile", (k_geo_tile<9>), nt, DRESSI_TILE_PIX, lds, st, vattr, V, tris, T, pc4, vp, H, W,
-                      cull, tri_id, b2, ntx, fl, grad_gbuf, gbi, gbo, ipart, rpart, ctx->skip_empty);
+            DR_LAUNCH("k_geo_tile", (k_geo_tile<9>), nt + lj.nb, DRESSI_TILE_PIX, lds, st, vattr, V, tris, T, pc4, vp,
+                      H, W, cull, tri_id, b2, ntx, fl, grad_gbuf, gbi, gbo, ipart, rpart, ctx->skip_empty, lj, nt);
     } else {
         dr_interp_bwd_tiles(vattr, 1, V, Cv, tris, T, tri_id, bary, 1, 1, H, W, fl, grad_gbuf, grad_bary_in,
                             grad_bary, ipart, ctx->skip_empty, st);
@@ -2083,6 +2029,8 @@ extern "C" int dressi_geometry_bwd(dressi_ctx *ctx, const float *pos, const floa
             DR_LAUNCH("k_rast_bwd_tile", (k_rast_bwd_tile), nt, DRESSI_TILE_PIX, sizeof(float) * 9 * DRESSI_TILE_PIX,
                       st, pc4, tris, vp, V, T, H, W, 1, cull, 0, tri_id, fl, ntx, nt, gbo, nullptr, rpart);
     }
+    // a whole step's list jobs not run yet: the per-vertex pass reads the lists
+    dr_flush_list_jobs(ctx, st);
     dr_geo_vertex(Cv, pos, tris, pos_clip, vp, V, H, W, tt, ipart, rpart, adjacency_view(adj, V), mvp, vert_view,
                   grad_vattr, grad_pos_clip, gpos_t, gacc, grad_pos, st);
     return dressi_launch_check(ctx, "geometry_bwd");
@@ -2195,17 +2143,86 @@ extern "C" int dressi_packed_step(dressi_ctx *ctx, const dressi_packed_scene *sc
     if (tex && (!b->inv || !b->inv_rec || !b->grad_tex))
         return dressi_fail(ctx, DRESSI_EINVAL, "packed_step: the textured step needs inv, inv_rec and grad_tex");
     const int V = sc->V, T = sc->T, H = b->H, W = b->W, Cv = sc->Cv;
-    int rc = dressi_geometry_fwd(ctx, b->pos, sc->tris, V, T, b->extra, b->adj, b->mvp, 1, b->vattr, b->pos_clip,
-                                 H, W, 0, b->tri_id, b->bary, b->index, stream);
-    if (rc) return rc;
-    rc = dressi_packed_forward(ctx, sc, b->tri_id, b->bary, 1, H, W, b->gbuf, b->uvbuf, b->samp, b->color, b->sil,
-                               b->edge, b->inv, stream);
-    if (rc) return rc;
-    rc = dressi_packed_backward(ctx, sc, b->tri_id, 1, H, W, b->gbuf, b->uvbuf, b->samp, b->color, b->sil,
-                                b->target, nullptr, b->loss, nullptr, nullptr, b->grad_gbuf, b->grad_samp,
-                                b->grad_bary_uv, b->inv, b->inv_rec, b->grad_tex, stream);
-    if (rc) return rc;
-    return dressi_geometry_bwd(ctx, b->pos, b->vattr, V, Cv, sc->tris, T, b->pos_clip, b->mvp, nullptr, nullptr,
-                               nullptr, 0, H, W, 0, b->tri_id, b->bary, b->grad_gbuf, tex ? b->grad_bary_uv : nullptr,
-                               b->index, b->adj, b->grad_vattr, b->grad_bary, b->grad_pos_clip, b->grad_pos, stream);
+    hipStream_t st = (hipStream_t)stream;
+    // With the binless rasterizer and a two-pass scan of the record counts,
+    // the triangle -> tile lists are built by four jobs run in the launches
+    // of the packed forward (the counts' chunk sums), the packed backward
+    // (the scan), the texel gather (the fill) and the per-tile geometry
+    // adjoint (the ranking); jobs without such a launch run on their own
+    // before the per-vertex adjoint.  Otherwise the calls in sequence.
+    const int64_t nchunk = ((int64_t)T + SCAN_CHUNK - 1) / SCAN_CHUNK;
+    const bool jobs = ctx->hard_raster == 3 && b->adj && V > 0 && T > 16384 && nchunk <= SCAN_DIRECT_MAX &&
+                      b->pos_clip && b->tri_id && b->bary && b->index && b->pos && b->mvp && b->vattr &&
+                      H > 0 && W > 0 && H <= 32767 && W <= 32767 && T < 0x7fffffff;
+    int rc;
+    ListJob j[4];   // taken by the calls below (so it lives until the function's end)
+    if (!jobs) {
+        rc = dressi_geometry_fwd(ctx, b->pos, sc->tris, V, T, b->extra, b->adj, b->mvp, 1, b->vattr, b->pos_clip, H,
+                                 W, 0, b->tri_id, b->bary, b->index, stream);
+    } else {
+        // scratch: what the packed backward and the geometry adjoints take
+        // (from the arena's start), then the fragment index's temporary, which
+        // lives until the last job
+        Carver cg;
+        size_t og[4];
+        geometry_scratch(H, W, V, Cv, cg, og);
+        const size_t off = (std::max(cg.off, dr_packed_bwd_scratch(sc, 1, H, W, tex)) + 255) / 256 * 256;
+        if ((rc = dressi_scratch(ctx, off + dressi_fragindex_tmp_bytes(1, 1, H, W, T), st))) return rc;
+        void *tmp = static_cast<char *>(ctx->scratch) + off;
+        const VertexStageArgs vs{b->pos, b->extra, b->mvp, b->adj, b->extra ? 9 : 6, b->vattr};
+        rc = direct_indexed(ctx, b->pos_clip, sc->tris, 1, V, T, H, W, 0, b->tri_id, b->bary, b->index, st, &vs, tmp,
+                            false);
+        if (rc) return rc;
+        FragLists fl;
+        TriTiles tt;
+        dressi_fragindex_view(b->index, 1, 1, H, W, T, fl, tt);
+        const int nt = tiles_x(W) * tiles_y(H);
+        const int64_t ne = (int64_t)nt * DRESSI_TILE_PIX;
+        int2 *unsorted = reinterpret_cast<int2 *>(static_cast<char *>(tmp) +
+                                                  (dressi_scan_tmp_bytes(T) + 255) / 256 * 256);
+        int32_t *nlong = reinterpret_cast<int32_t *>(unsorted + ne);
+        int64_t *longk = reinterpret_cast<int64_t *>(nlong + 2);
+        int2 *sbuf = reinterpret_cast<int2 *>(longk + tt_long_cap(ne));
+        for (int k = 0; k < 4; k++) {
+            j[k].in = ctx->counters;
+            j[k].out = tt.offsets;
+            j[k].n = T;
+            j[k].sums = static_cast<int32_t *>(tmp);
+            j[k].fl = fl;
+            j[k].K = 1;
+            j[k].T = T;
+            j[k].nt = nt;
+            j[k].cap = (int)std::min<size_t>(tt_long_cap(ne), 0x7fffffff);
+            j[k].counts = ctx->counters;
+            j[k].nlong = nlong;
+            j[k].unsorted = unsorted;
+            j[k].entries = tt.entries;
+            j[k].sbuf = sbuf;
+            j[k].longk = longk;
+        }
+        j[0].kind = LJ_SCAN_REDUCE, j[0].nb = (int)nchunk;
+        j[1].kind = LJ_SCAN_APPLY, j[1].nb = (int)nchunk;
+        j[2].kind = LJ_TT_FILL, j[2].nb = nt;
+        j[3].kind = LJ_TT_RANK, j[3].nb = (int)std::min<int64_t>((ne + 255) / 256, 4096);
+        ctx->list_job = j;
+        ctx->n_list_jobs = 4;
+    }
+    if (!rc)
+        rc = dressi_packed_forward(ctx, sc, b->tri_id, b->bary, 1, H, W, b->gbuf, b->uvbuf, b->samp, b->color,
+                                   b->sil, b->edge, b->inv, stream);
+    if (!rc)
+        rc = dressi_packed_backward(ctx, sc, b->tri_id, 1, H, W, b->gbuf, b->uvbuf, b->samp, b->color, b->sil,
+                                    b->target, nullptr, b->loss, nullptr, nullptr, b->grad_gbuf, b->grad_samp,
+                                    b->grad_bary_uv, b->inv, b->inv_rec, b->grad_tex, stream);
+    if (!rc)
+        rc = dressi_geometry_bwd(ctx, b->pos, b->vattr, V, Cv, sc->tris, T, b->pos_clip, b->mvp, nullptr, nullptr,
+                                 nullptr, 0, H, W, 0, b->tri_id, b->bary, b->grad_gbuf,
+                                 tex ? b->grad_bary_uv : nullptr, b->index, b->adj, b->grad_vattr, b->grad_bary,
+                                 b->grad_pos_clip, b->grad_pos, stream);
+    // jobs left by a call that stopped early run here (they keep the
+    // counters' zero); none are left for later calls
+    if (ctx->n_list_jobs > 0) dr_flush_list_jobs(ctx, st);
+    ctx->list_job = nullptr;
+    ctx->n_list_jobs = 0;
+    return rc;
 }

@@ -1073,11 +1073,16 @@ __global__ void __launch_bounds__(256)
                  const float2 *__restrict__ bary, int64_t npix, int64_t n, float *__restrict__ gbuf,
                  float *__restrict__ uvbuf, float *__restrict__ samp, float *__restrict__ color,
                  float *__restrict__ sil, uint8_t *__restrict__ edge, int32_t *__restrict__ inv, int64_t ncells,
-                 int skip_empty) {
+                 int skip_empty, ListJob lj, int nmain) {
+    // workgroups past the pass's own run a list-building job of the step
+    if ((int)blockIdx.x >= nmain) {
+        list_job_block(lj, (int)blockIdx.x - nmain);
+        return;
+    }
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (inv) {
         // the backward's inverse-UV map starts at -1 (16-byte aligned, int4 rows)
-        const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+        const int64_t stride = (int64_t)nmain * blockDim.x;
         for (int64_t c = i; c < ncells / 4; c += stride)
             reinterpret_cast<int4 *>(inv)[c] = make_int4(-1, -1, -1, -1);
         for (int64_t c = ncells / 4 * 4 + i; c < ncells; c += stride) inv[c] = -1;
@@ -1190,13 +1195,18 @@ __global__ void __launch_bounds__(256)
                  const float *__restrict__ weight, float w_uniform, float *__restrict__ grad_color,
                  float *__restrict__ grad_sil, float *__restrict__ g_gbuf, float *__restrict__ g_samp,
                  float2 *__restrict__ g_bary_uv, int32_t *__restrict__ inv, int4 *__restrict__ rec,
-                 float *__restrict__ partial, int skip_empty) {
+                 float *__restrict__ partial, int skip_empty, ListJob lj, int nmain) {
+    // workgroups past the pass's own run a list-building job of the step
+    if ((int)blockIdx.x >= nmain) {
+        list_job_block(lj, (int)blockIdx.x - nmain);
+        return;
+    }
     __shared__ float red[256];
     float acc = 0.0f;
     // one pixel per lane (grid-stride when the image has more pixels than the
     // grid has lanes: each lane's loss terms are added in pixel order)
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
+         i += (int64_t)nmain * blockDim.x) {
         // L2 loss term and its gradient (the loss stage's arithmetic)
         const float4 tg = target[i];
         const float d0 = color[3 * i] - tg.x, d1 = color[3 * i + 1] - tg.y, d2 = color[3 * i + 2] - tg.z;
@@ -1393,13 +1403,25 @@ extern "C" int dressi_packed_forward(dressi_ctx *ctx, const dressi_packed_scene 
     hipStream_t st = (hipStream_t)stream;
     const int g = (int)((n + 255) / 256);
     const float2 *b2 = reinterpret_cast<const float2 *>(bary);
+    const ListJob lj = dr_take_list_job(ctx);
     if (tex)
-        DR_LAUNCH("k_packed_fwd", (k_packed_fwd<6, true>), g, 256, 0, st, sc->mode, *sc, tri_id, b2, npix, n, gbuf,
-                  uvbuf, samp, color, sil, edge, inv, ncells, ctx->skip_empty);
+        DR_LAUNCH("k_packed_fwd", (k_packed_fwd<6, true>), g + lj.nb, 256, 0, st, sc->mode, *sc, tri_id, b2, npix, n,
+                  gbuf, uvbuf, samp, color, sil, edge, inv, ncells, ctx->skip_empty, lj, g);
     else
-        DR_LAUNCH("k_packed_fwd", (k_packed_fwd<9, false>), g, 256, 0, st, sc->mode, *sc, tri_id, b2, npix, n, gbuf,
-                  uvbuf, samp, color, sil, edge, inv, ncells, ctx->skip_empty);
+        DR_LAUNCH("k_packed_fwd", (k_packed_fwd<9, false>), g + lj.nb, 256, 0, st, sc->mode, *sc, tri_id, b2, npix,
+                  n, gbuf, uvbuf, samp, color, sil, edge, inv, ncells, ctx->skip_empty, lj, g);
     return dressi_launch_check(ctx, "packed_forward");
+}
+
+size_t dr_packed_bwd_scratch(const dressi_packed_scene *sc, int B, int H, int W, bool grad_tex) {
+    const int64_t n = (int64_t)B * H * W;
+    const int64_t nb = n > 0 ? std::min<int64_t>((n + 255) / 256, PACKED_MAX_BLOCKS) : 1;
+    Carver c;
+    c.take(sizeof(float) * (size_t)nb);
+    const int64_t cells =
+        sc->mode == DRESSI_SHADE_PHONG ? (int64_t)tex_faces(sc->td) * sc->td.Ht * sc->td.Wt : 0;
+    if (grad_tex) c.take(dressi_invuv_part_bytes(cells, 4, B));
+    return c.off;
 }
 
 extern "C" int dressi_packed_backward(dressi_ctx *ctx, const dressi_packed_scene *sc, const int32_t *tri_id,
@@ -1439,20 +1461,22 @@ extern "C" int dressi_packed_backward(dressi_ctx *ctx, const dressi_packed_scene
     float2 *gb = reinterpret_cast<float2 *>(grad_bary_uv);
     if (n == 0) {
         dressi_fill_f32(partial, 0.0f, 1, st);
-    } else if (tex) {
-        DR_LAUNCH("k_packed_bwd", (k_packed_bwd<6, true>), (int)nb, 256, 0, st, sc->mode, *sc, tri_id, npix, n, gbuf,
-                  uvbuf, samp, color, sil, t4, weight, w, grad_color, grad_sil, grad_gbuf, grad_samp, gb, inv,
-                  static_cast<int4 *>(inv_rec), partial, ctx->skip_empty);
     } else {
-        DR_LAUNCH("k_packed_bwd", (k_packed_bwd<9, false>), (int)nb, 256, 0, st, sc->mode, *sc, tri_id, npix, n,
-                  gbuf, uvbuf, samp, color, sil, t4, weight, w, grad_color, grad_sil, grad_gbuf, grad_samp, gb, inv,
-                  nullptr, partial, ctx->skip_empty);
+        const ListJob job = dr_take_list_job(ctx);
+        if (tex)
+            DR_LAUNCH("k_packed_bwd", (k_packed_bwd<6, true>), (int)nb + job.nb, 256, 0, st, sc->mode, *sc, tri_id,
+                      npix, n, gbuf, uvbuf, samp, color, sil, t4, weight, w, grad_color, grad_sil, grad_gbuf,
+                      grad_samp, gb, inv, static_cast<int4 *>(inv_rec), partial, ctx->skip_empty, job, (int)nb);
+        else
+            DR_LAUNCH("k_packed_bwd", (k_packed_bwd<9, false>), (int)nb + job.nb, 256, 0, st, sc->mode, *sc, tri_id,
+                      npix, n, gbuf, uvbuf, samp, color, sil, t4, weight, w, grad_color, grad_sil, grad_gbuf,
+                      grad_samp, gb, inv, nullptr, partial, ctx->skip_empty, job, (int)nb);
     }
     const LossJob lj{partial, (int)nb, weight ? 1.0f : w, loss};
     if (grad_tex) {
         // the texel gather, with the loss's last sum in an extra workgroup of its launch
         dr_gather_invrec(sc->td, B, npix, inv, static_cast<const int4 *>(inv_rec), at<float>(ctx->scratch, o_g),
-                         grad_tex, st, ctx->iv_rows, lj);
+                         grad_tex, st, ctx->iv_rows, lj, dr_take_list_job(ctx));
     } else {
         DR_LAUNCH("k_loss_sum", (k_loss_sum), 1, LOSS_BS, 0, st, lj.partial, lj.nb, lj.scale, lj.loss);
     }

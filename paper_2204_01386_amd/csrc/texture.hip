@@ -257,7 +257,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(((R ==
     k_invuv_gather(dressi_tex_desc td, const float *__restrict__ coord, const int32_t *__restrict__ tri_id,
                    int64_t npix, int S, int nsplit, const int32_t *__restrict__ inv,
                    const float *__restrict__ grad_out, float *__restrict__ out, int xcd,
-                   const int4 *__restrict__ rec, LossJob lj) {
+                   const int4 *__restrict__ rec, LossJob lj, ListJob job, int jcols) {
     static_assert(!REC || CT == 4, "records hold an RGBA gradient");
     // per halo cell of each slice of the group: the winner's four tap
     // coordinates, bilinear fractions (fx < 0: no winner, or one on another
@@ -279,9 +279,17 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(((R ==
     // the grid (rows of blocks), so they are fetched into one L2
     // with a loss job, the grid's last column of workgroups is the job's (its
     // first workgroup runs it, the others exit)
-    const int gxb = (int)gridDim.x - (lj.loss ? 1 : 0);
-    if (lj.loss && (int)blockIdx.x == gxb) {
-        if (blockIdx.y == 0 && blockIdx.z == 0) loss_sum_block(lj, reinterpret_cast<float *>(&cfr[0][0]));
+    // and with a list-building job of the step, the columns after it are the
+    // job's workgroups
+    const int lc = lj.loss ? 1 : 0;
+    const int gxb = (int)gridDim.x - lc - jcols;
+    if ((int)blockIdx.x >= gxb) {
+        if (lj.loss && (int)blockIdx.x == gxb) {
+            if (blockIdx.y == 0 && blockIdx.z == 0) loss_sum_block(lj, reinterpret_cast<float *>(&cfr[0][0]));
+            return;
+        }
+        list_job_block(job, (((int)blockIdx.x - gxb - lc) * (int)gridDim.y + (int)blockIdx.y) * (int)gridDim.z +
+                                (int)blockIdx.z);
         return;
     }
     // (the divisions stay off the common path: with many short workgroups
@@ -471,23 +479,24 @@ __global__ void k_invuv_reduce(const float *__restrict__ part, int nsplit, int64
 template <int SG, int R>
 static void launch_gather_r(int ct, dim3 g, hipStream_t st, const dressi_tex_desc &td, const float *coord,
                             const int32_t *tri_id, int64_t npix, int S, int nsplit, const int32_t *inv,
-                            const float *grad_out, float *dst, int xcd, const int4 *rec, LossJob lj) {
+                            const float *grad_out, float *dst, int xcd, const int4 *rec, LossJob lj,
+                            const ListJob &job, int jcols) {
     constexpr int nt = IvGeom<SG, R>::NT;
     if (rec)
         DR_LAUNCH("k_invuv_gather", (k_invuv_gather<4, SG, R, true>), g, nt, 0, st, td, coord, tri_id, npix, S,
-                  nsplit, inv, grad_out, dst, xcd, rec, lj);
+                  nsplit, inv, grad_out, dst, xcd, rec, lj, job, jcols);
     else if (ct == 4)
         DR_LAUNCH("k_invuv_gather", (k_invuv_gather<4, SG, R>), g, nt, 0, st, td, coord, tri_id, npix, S,
-                  nsplit, inv, grad_out, dst, xcd, rec, lj);
+                  nsplit, inv, grad_out, dst, xcd, rec, lj, job, jcols);
     else if (ct == 3)
         DR_LAUNCH("k_invuv_gather", (k_invuv_gather<3, SG, R>), g, nt, 0, st, td, coord, tri_id, npix, S,
-                  nsplit, inv, grad_out, dst, xcd, rec, lj);
+                  nsplit, inv, grad_out, dst, xcd, rec, lj, job, jcols);
     else if (ct == 8)
         DR_LAUNCH("k_invuv_gather", (k_invuv_gather<8, SG, R>), g, nt, 0, st, td, coord, tri_id, npix, S,
-                  nsplit, inv, grad_out, dst, xcd, rec, lj);
+                  nsplit, inv, grad_out, dst, xcd, rec, lj, job, jcols);
     else
         DR_LAUNCH("k_invuv_gather", (k_invuv_gather<0, SG, 1>), g, nt, 0, st, td, coord, tri_id, npix, S,
-                  nsplit, inv, grad_out, dst, xcd, rec, lj);
+                  nsplit, inv, grad_out, dst, xcd, rec, lj, job, jcols);
 }
 
 // Large textures take the XCD-contiguous block order and two texel rows per
@@ -509,19 +518,21 @@ static int gather_rows(int rows, int ct, int S, const dressi_tex_desc &td, bool 
 static void launch_gather(int rows, int ct, int64_t gx, int64_t ty_cells, int gz, hipStream_t st,
                           const dressi_tex_desc &td, const float *coord, const int32_t *tri_id, int64_t npix,
                           int S, int nsplit, const int32_t *inv, const float *grad_out, float *dst,
-                          const int4 *rec, LossJob lj) {
+                          const int4 *rec, LossJob lj, const ListJob &job) {
     const int R = gather_rows(rows, ct, S, td, rec != nullptr);
     const int xcd = (int64_t)td.Ht * td.Wt >= IV_LARGE_CELLS;
-    dim3 g((unsigned)(gx + (lj.loss ? 1 : 0)), (unsigned)((ty_cells + 16 * R - 1) / (16 * R)), (unsigned)gz);
+    const int64_t gy = (ty_cells + 16 * R - 1) / (16 * R);
+    const int jcols = job.nb > 0 ? (int)((job.nb + gy * gz - 1) / (gy * gz)) : 0;
+    dim3 g((unsigned)(gx + (lj.loss ? 1 : 0) + jcols), (unsigned)gy, (unsigned)gz);
     if (R == 4)
         launch_gather_r<DRESSI_IV_SG, 4>(ct, g, st, td, coord, tri_id, npix, S, nsplit, inv, grad_out, dst, xcd,
-                                          rec, lj);
+                                          rec, lj, job, jcols);
     else if (R == 2)
         launch_gather_r<DRESSI_IV_SG, 2>(ct, g, st, td, coord, tri_id, npix, S, nsplit, inv, grad_out, dst, xcd,
-                                          rec, lj);
+                                          rec, lj, job, jcols);
     else
         launch_gather_r<DRESSI_IV_SG, 1>(ct, g, st, td, coord, tri_id, npix, S, nsplit, inv, grad_out, dst, xcd,
-                                          rec, lj);
+                                          rec, lj, job, jcols);
 }
 
 // float4 rows need 16-byte aligned bases
@@ -599,13 +610,14 @@ static void tex_bwd_pixels(const float *tex, const dressi_tex_desc &td, const fl
 // grid as well and the parts summed afterwards in `part`.
 static void tex_gather(const dressi_tex_desc &td, const float *coord, const int32_t *tri_id, int64_t npix,
                        int S, const int32_t *inv, const float *grad_out, float *part, float *grad_tex,
-                       hipStream_t st, int rows, const int4 *rec = nullptr, LossJob lj = LossJob{}) {
+                       hipStream_t st, int rows, const int4 *rec = nullptr, LossJob lj = LossJob{},
+                       const ListJob &job = ListJob{}) {
     const int64_t cells = (int64_t)tex_faces(td) * td.Ht * td.Wt;
     const int nsplit = dressi_invuv_nsplit(cells, S);
     float *dst = nsplit > 1 ? part : grad_tex;
     const int ct = rec ? 4 : (aligned16(grad_out, dst) ? td.Ct : 0);
     launch_gather(rows, ct, (td.Wt + IV_T - 1) / IV_T, td.Ht, tex_faces(td) * nsplit, st, td, coord, tri_id,
-                  npix, S, nsplit, inv, grad_out, dst, rec, lj);
+                  npix, S, nsplit, inv, grad_out, dst, rec, lj, job);
     if (nsplit > 1) {
         int64_t ne = cells * td.Ct;
         DR_LAUNCH("k_invuv_reduce", (k_invuv_reduce), (int)((ne + 255) / 256), 256, 0, st, part, nsplit, ne,
@@ -719,8 +731,8 @@ extern "C" int dressi_texture_grad_invuv(dressi_ctx *ctx, const dressi_tex_desc 
 }
 
 void dr_gather_invrec(const dressi_tex_desc &td, int S, int64_t npix, const int32_t *inv, const int4 *rec,
-                      float *part, float *grad_tex, hipStream_t st, int rows, LossJob lj) {
-    tex_gather(td, nullptr, nullptr, npix, S, inv, nullptr, part, grad_tex, st, rows, rec, lj);
+                      float *part, float *grad_tex, hipStream_t st, int rows, LossJob lj, const ListJob &job) {
+    tex_gather(td, nullptr, nullptr, npix, S, inv, nullptr, part, grad_tex, st, rows, rec, lj, job);
 }
 
 extern "C" int dressi_texture_grad_invrec(dressi_ctx *ctx, const dressi_tex_desc *td, int S, int H, int W,
