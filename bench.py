@@ -137,11 +137,11 @@ def scene_for(cfg):
 FETCH_SCALE, WRITE_SCALE = 262144.0 / 131083.5, 1.0
 TRAFFIC = {
     "k_invuv_gather": {"src": "paper_2204_01386_amd/csrc/texture.hip",
-                       "sha": "6041a3facb57452af9443ac2c62f9880afacaa05f0bca3f9d63ba987c7c2ab41",
-                       "fetch_kib": 10427.875, "write_kib": 16384.03125},
+                       "sha": "c152c7215b4175a8581336317d50255a6df16017110a081b438998f3ec178ce4",
+                       "fetch_kib": 10434.0625, "write_kib": 16384.03125},
     "k_packed_bwd": {"src": "paper_2204_01386_amd/csrc/shade.hip",
-                     "sha": "9f41c8f1b90b25364e9a5f58edd821040ea3a449e445ea0878e3a53b135a74c3",
-                     "fetch_kib": 10622.4375, "write_kib": 7253.03125},
+                     "sha": "d294fd08a604b8564d2e85916e3fd85935d080b02776a2876d1a9dbe346b2797",
+                     "fetch_kib": 10408.875, "write_kib": 7253.0},
 }
 
 
