@@ -2076,6 +2076,15 @@ extern "C" size_t dressi_limits_scratch_bytes(const dressi_limits *l) {
     need = std::max(need, dr_need_optim(*l));
     need = std::max(need, dr_need_pbs(*l));
     need = std::max(need, 2 * (size_t)std::max(l->B, 0) * std::max(l->H, 0) * std::max(l->W, 0));  // softras
+    // the whole packed step of one image: the packed backward's and the
+    // geometry adjoints' scratch, then the fragment index's temporary
+    if (l->K <= 1 && l->H > 0 && l->W > 0) {
+        Carver cg;
+        size_t og[4];
+        geometry_scratch(l->H, l->W, l->V, 9, cg, og);
+        const size_t off = (std::max(cg.off, dr_need_shade(*l)) + 255) / 256 * 256;
+        need = std::max(need, off + dressi_fragindex_tmp_bytes(1, 1, l->H, l->W, l->T));
+    }
     return need;
 }
 

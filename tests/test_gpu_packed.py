@@ -480,3 +480,36 @@ def test_packed_step_argument_checks(Bd):
         setattr(b, f, keep)
     torch.cuda.synchronize()
     assert np.array_equal(host(st.g_pos), before)
+
+
+def test_packed_step_captured_after_reserve_limits(Bd):
+    """A fresh context sized once by dressi_reserve_limits (K = 1, one view
+    of the step's shapes) captures the whole packed step, with the binless
+    rasterizer and its co-launched list jobs, as its first call; the replays
+    give bitwise the step's eager results."""
+    import ctypes as C
+    from paper_2204_01386_amd.pipeline import Step, make_target
+    s = scenes.config2()
+    st = Step(s, target=make_target(s))
+    st.hard_raster = 3
+    st.run()
+    torch.cuda.synchronize()
+    ref = {k: host(v).copy() for k, v in st.grads().items()}
+    lim = Bd.Limits(B=1, V=st.V, T=st.T, H=st.H, W=st.W, K=1, r=0.0, Va=st.V, C=st.Cv,
+                    tex_cells=st.desc.Ht * st.desc.Wt, tex_channels=4, tex_slices=1, jitter=0)
+    ca = Bd.Context(torch.cuda.current_device())
+    ca.reserve_limits(lim)
+    ca.tune(Bd.TUNE_HARD_RASTER, 3)
+    ca.tune(Bd.TUNE_EMPTY_SLOTS, 1)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        ca.check(Bd._lib.dressi_packed_step(ca.handle, C.byref(st._pscene), C.byref(st._step_bufs), Bd._stream()),
+                 "packed_step")
+    for rep in range(3):
+        for v in st.grads().values():
+            v.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        for k, v in st.grads().items():
+            assert np.array_equal(host(v), ref[k]), (rep, k)
