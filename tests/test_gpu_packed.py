@@ -423,7 +423,21 @@ def test_geometry_fwd_matches_stage_and_rasterization(Bd, views):
     assert bool((tid == 5).all())
 
 
-@pytest.mark.parametrize("which", ["config1", "config2"])
+def _lambert_large():
+    """Lambert icosphere s6 (81,920 triangles) at 256 x 256: enough
+    triangles for the step's co-launched list jobs without a texture gather
+    (the ranking then runs on its own before the per-vertex adjoint)."""
+    from paper_2204_01386_amd.scenes import Scene, icosphere, view_proj
+    rng = np.random.default_rng(4)
+    p, tris = icosphere(6)
+    color = rng.random((len(p), 3)).astype(np.float32)
+    tpos = p + rng.normal(0.0, 0.02, p.shape)
+    eyes = np.array([[0.3, 0.2, 3.0]])
+    return Scene("icosphere6-256", p.astype(np.float32), tris, view_proj(eyes), eyes.astype(np.float32), 256, 256,
+                 1, 0.0, "lambert", color=color, target_pos=tpos.astype(np.float32), target_color=color)
+
+
+@pytest.mark.parametrize("which", ["config1", "config2", "lambert_large"])
 @pytest.mark.parametrize("hr", [0, 3])
 def test_packed_step_matches_its_calls(Bd, which, hr):
     """dressi_packed_step gives bitwise the forward values, the loss and
@@ -431,7 +445,7 @@ def test_packed_step_matches_its_calls(Bd, which, hr):
     packed forward and backward, geometry adjoints), with the binless and a
     binned rasterizer, eagerly and over graph replays."""
     from paper_2204_01386_amd.pipeline import Step, make_target
-    s = _scene(which)
+    s = _lambert_large() if which == "lambert_large" else _scene(which)
     res = []
     for whole in (False, True):
         st = Step(s, target=make_target(s))
