@@ -387,14 +387,18 @@ __device__ __forceinline__ void tt_rank_block(const FragLists &fl, int K, int T,
 }
 
 enum { LJ_NONE = 0, LJ_SCAN_REDUCE, LJ_SCAN_APPLY, LJ_TT_FILL, LJ_TT_RANK };
+// One job's arguments.  in: the record counts [n] (the scan's input); out:
+// the lists' offsets [n + 1] (the scan's output, which the fill and the
+// ranking read); n: the number of (view, triangle) keys; sums: the chunk
+// sums; the rest as k_tt_fill and k_tt_rank take them.
 struct ListJob {
     int kind = LJ_NONE;
     int nb = 0;                         // workgroups
-    const int32_t *in = nullptr;        // scan: counts [n], sums, offsets [n + 1]
+    const int32_t *in = nullptr;
     int32_t *out = nullptr;
     int64_t n = 0;
     int32_t *sums = nullptr;
-    FragLists fl{};                     // lists
+    FragLists fl{};
     int K = 1, T = 0, nt = 1, cap = 0;
     int32_t *counts = nullptr, *nlong = nullptr;
     int2 *unsorted = nullptr, *entries = nullptr, *sbuf = nullptr;
