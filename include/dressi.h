@@ -636,10 +636,14 @@ int dressi_geometry_bwd(dressi_ctx *ctx, const float *pos, const float *vattr, i
  * the pixel records, inv_rec and grad_tex required) and dressi_geometry_bwd
  * (no viewports; grad_bary_in = grad_bary_uv when textured), the same values
  * as those calls in that order.  Because the library sees the whole step it
- * can launch independent kernels of different stages together: the
- * fragment index's triangle -> tile lists are built in the launches of the
- * shading passes, the texel gather and the per-tile geometry adjoint.
- * scene->vattr must be b->vattr (written by the step).  Every buffer is the
+ * can launch independent kernels of different stages together: with the
+ * binless rasterizer (DRESSI_TUNE_HARD_RASTER = 3), adj given and more than
+ * 16,384 triangles, the fragment index's triangle -> tile lists are built in
+ * the launches of the shading passes, the texel gather and the per-tile
+ * geometry adjoint (otherwise the calls run in sequence).  The arena then
+ * holds the index's temporary beside the later calls' scratch
+ * (dressi_reserve_limits with K = 1 sizes it).  scene->vattr must be
+ * b->vattr (written by the step).  Every buffer is the
  * caller's.  Errors: DRESSI_EINVAL, with nothing launched, for a null scene
  * or buffer set, a scene->vattr other than b->vattr or a textured step
  * without inv, inv_rec and grad_tex; otherwise the code of the first of the
