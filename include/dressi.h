@@ -22,7 +22,9 @@
  *   share a context must be issued on one stream (they share its scratch).
  * - Return value: DRESSI_OK or a negative status; dressi_last_error() gives a
  *   message.  Errors are detected on the host (arguments, scratch) before any
- *   launch; a rejected call launches nothing.  Bin-capacity overflow can only
+ *   launch; a rejected call launches nothing (dressi_packed_step, which
+ *   chains four calls, stops at the first that refuses: see there).
+ *   Bin-capacity overflow can only
  *   be seen on the device: it is recorded there and reported by
  *   dressi_check_status(), and the affected outputs are then invalid.
  *
