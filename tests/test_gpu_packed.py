@@ -527,3 +527,36 @@ def test_packed_step_captured_after_reserve_limits(Bd):
         torch.cuda.synchronize()
         for k, v in st.grads().items():
             assert np.array_equal(host(v), ref[k]), (rep, k)
+
+
+def test_packed_step_refused_midway_leaves_the_context_clean(Bd):
+    """A whole step whose packed backward refuses its arguments (here a
+    Lambert step without grad_gbuf), after the geometry forward and the
+    packed forward have run with the list jobs queued, returns EINVAL, runs
+    the jobs left (the fragment index complete, the zero-kept counters back
+    at zero) and leaves none queued: the next steps match the results of a
+    step run before the refused call."""
+    import ctypes as C
+    from paper_2204_01386_amd.pipeline import Step, make_target
+    s = _lambert_large()
+    ref_st = Step(s, target=make_target(s))
+    ref_st.hard_raster = 3
+    ref_st.run()
+    torch.cuda.synchronize()
+    ref = {k: host(v).copy() for k, v in ref_st.grads().items()}
+    st = Step(s, target=make_target(s))
+    st.hard_raster = 3
+    assert st._whole_step()
+    torch.cuda.synchronize()
+    b = st._step_bufs
+    keep = b.grad_gbuf
+    b.grad_gbuf = None
+    rc = Bd._lib.dressi_packed_step(st.ctx.handle, C.byref(st._pscene), C.byref(b), Bd._stream())
+    b.grad_gbuf = keep
+    assert rc == Bd.EINVAL
+    torch.cuda.synchronize()
+    for _ in range(2):
+        st.run()
+        torch.cuda.synchronize()
+        for k, v in st.grads().items():
+            assert np.array_equal(host(v), ref[k]), k
